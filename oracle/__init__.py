@@ -1,0 +1,203 @@
+"""Plain FP64 CPU oracle for the enriched DG velocity residual and the SIP
+Poisson operator (arXiv 1705.08813, Sec. 3-4).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark import this package; the product library
+never does, and it shares no code with the HIP path.
+
+The C part (dg_oracle.c) evaluates the operators element by element at every
+quadrature point from directly evaluated 1-D Lagrange products.  The Python
+modules next to it hold independent cross-checks used as pins:
+  dense.py  face-by-face dense assembly of the linear parts on tiny meshes;
+  kron.py   Kronecker-sum evaluation of the Poisson operator on box meshes;
+  solve.py  reference conjugate-gradient solve.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("Lx", ctypes.c_double), ("Lz", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("wall_amp", ctypes.c_double),
+        ("k_u", ctypes.c_int32), ("k_p", ctypes.c_int32),
+        ("nq_u", ctypes.c_int32), ("nq_p", ctypes.c_int32), ("nq_wn", ctypes.c_int32),
+        ("enrich_lower", ctypes.c_int32), ("enrich_upper", ctypes.c_int32), ("fully_periodic", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("kappa", ctypes.c_double), ("B", ctypes.c_double),
+        ("ip_factor_u", ctypes.c_double), ("ip_factor_p", ctypes.c_double),
+        ("wall_ip_mult", ctypes.c_double), ("theta", ctypes.c_double),
+    ]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        P = ctypes.POINTER(OrcParams)
+        L.orc_gauss.argtypes = [ctypes.c_int, _D, _D]
+        L.orc_gauss_lobatto.argtypes = [ctypes.c_int, _D]
+        L.orc_lagrange.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D, _D]
+        L.orc_lagrange.restype = None
+        L.orc_spalding.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.orc_vertex_eta.argtypes = [P, _D]
+        L.orc_vertex_eta.restype = None
+        L.orc_num_dofs.argtypes = [P, ctypes.c_int]
+        L.orc_num_dofs.restype = ctypes.c_int64
+        L.orc_num_enriched.argtypes = [P]
+        L.orc_num_enriched.restype = ctypes.c_int64
+        L.orc_velocity_residual.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
+        L.orc_poisson_apply.argtypes = [P, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
+        L.orc_poisson_diag.argtypes = [P, _I64, ctypes.c_int64, _D]
+        L.orc_psi_point.argtypes = [P, _D, ctypes.c_int64, _D, _D]
+        L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
+        _LIB = L
+    return _LIB
+
+
+def params(cfg) -> OrcParams:
+    """Oracle parameter struct from a MeshConfig (or any object/dict with the fields)."""
+    d = cfg if isinstance(cfg, dict) else cfg.as_dict()
+    p = OrcParams()
+    for name, _ in OrcParams._fields_:
+        setattr(p, name, d[name])
+    return p
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def gauss(n):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    if lib().orc_gauss(n, _ptr(x), _ptr(w)):
+        raise ValueError("bad n")
+    return x, w
+
+
+def gauss_lobatto(n):
+    x = np.zeros(n)
+    if lib().orc_gauss_lobatto(n, _ptr(x)):
+        raise ValueError("bad n")
+    return x
+
+
+def lagrange(nodes, t):
+    nodes = _f64(nodes)
+    n = len(nodes)
+    v = np.zeros(n)
+    d = np.zeros(n)
+    lib().orc_lagrange(n, _ptr(nodes), float(t), _ptr(v), _ptr(d))
+    return v, d
+
+
+def spalding(yplus, kappa=0.41, B=5.17):
+    U = ctypes.c_double()
+    dU = ctypes.c_double()
+    if lib().orc_spalding(float(yplus), kappa, B, ctypes.byref(U), ctypes.byref(dU)):
+        raise ValueError("bad y+")
+    return U.value, dU.value
+
+
+def vertex_eta(cfg):
+    p = params(cfg)
+    out = np.zeros(p.ny + 1)
+    lib().orc_vertex_eta(ctypes.byref(p), _ptr(out))
+    return out
+
+
+def num_dofs(cfg, field):
+    return int(lib().orc_num_dofs(ctypes.byref(params(cfg)), field))
+
+
+def num_enriched(cfg):
+    return int(lib().orc_num_enriched(ctypes.byref(params(cfg))))
+
+
+def _cells(cfg, cells):
+    p = params(cfg)
+    if cells is None:
+        cells = np.arange(p.nx * p.ny * p.nz, dtype=np.int64)
+    return np.ascontiguousarray(cells, dtype=np.int64)
+
+
+def velocity_residual(cfg, u, tau, cells=None, absmode=False):
+    """Residual r for the listed cells (others left zero).  Layout
+    [cell][component][node] then [enriched cell][component]."""
+    p = params(cfg)
+    u = _f64(u)
+    n = num_dofs(cfg, 0)
+    if u.size != n:
+        raise ValueError(f"u has {u.size} entries, expected {n}")
+    tau = _f64(tau) if tau is not None else np.zeros(1)
+    cells = _cells(cfg, cells)
+    r = np.zeros(n)
+    rc = lib().orc_velocity_residual(ctypes.byref(p), _ptr(u), _ptr(tau), cells.ctypes.data_as(_I64),
+                                     cells.size, _ptr(r), int(absmode))
+    if rc:
+        raise RuntimeError(f"orc_velocity_residual failed: {rc}")
+    return r
+
+
+def poisson_apply(cfg, x, cells=None, absmode=False):
+    p = params(cfg)
+    x = _f64(x)
+    n = num_dofs(cfg, 1)
+    if x.size != n:
+        raise ValueError(f"x has {x.size} entries, expected {n}")
+    cells = _cells(cfg, cells)
+    y = np.zeros(n)
+    rc = lib().orc_poisson_apply(ctypes.byref(p), _ptr(x), cells.ctypes.data_as(_I64), cells.size, _ptr(y),
+                                 int(absmode))
+    if rc:
+        raise RuntimeError(f"orc_poisson_apply failed: {rc}")
+    return y
+
+
+def poisson_diag(cfg, cells=None):
+    p = params(cfg)
+    cells = _cells(cfg, cells)
+    d = np.zeros(num_dofs(cfg, 1))
+    rc = lib().orc_poisson_diag(ctypes.byref(p), cells.ctypes.data_as(_I64), cells.size, _ptr(d))
+    if rc:
+        raise RuntimeError(f"orc_poisson_diag failed: {rc}")
+    return d
+
+
+def psi_point(cfg, tau, e, xi):
+    p = params(cfg)
+    tau = _f64(tau)
+    xi = _f64(xi)
+    out = np.zeros(4)
+    rc = lib().orc_psi_point(ctypes.byref(p), _ptr(tau), int(e), _ptr(xi), _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_psi_point failed: {rc}")
+    return out
+
+
+def cell_map(cfg, e, xi):
+    p = params(cfg)
+    xi = _f64(xi)
+    X = np.zeros(3)
+    det = ctypes.c_double()
+    lib().orc_cell_map(ctypes.byref(p), int(e), _ptr(xi), _ptr(X), ctypes.byref(det))
+    return X, det.value
