@@ -1,0 +1,186 @@
+/*
+ * dgwm.h -- C ABI of the MI355X (gfx950) library for the enriched
+ * discontinuous-Galerkin operators of the multiscale RANS/LES wall model of
+ * Krank, Kronbichler & Wall (arXiv 1705.08813).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Return value: 0 on success, a negative DG_ERR_* code otherwise; the
+ *    message of the last failure on the calling thread is dg_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - Device pointers are HIP device (or managed) addresses on the device that
+ *    is current when the call is made; they must be 256-byte aligned and
+ *    must not alias one another unless stated.  Host pointers are ordinary
+ *    CPU memory.  The library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream).  Apply calls only enqueue work and return; results are ready
+ *    when the stream has drained.  Inputs are never modified; outputs are
+ *    fully overwritten (never accumulated).
+ *  - The library performs no device allocation: every device buffer,
+ *    including the mesh tables and solver work vectors, lives in workspace
+ *    that the caller allocates (e.g. a torch uint8 tensor) and keeps alive
+ *    until dg_destroy_mesh / the end of the call that uses it.
+ *
+ * Mesh and numbering
+ * ------------------
+ *  Channel 0<=x<=Lx, -1<=y<=1, 0<=z<=Lz, periodic in x and z, no-slip walls at
+ *  y = -1 (optionally displaced to y_w(x) = -1 + wall_amp cos(2 pi x/Lx)) and
+ *  y = +1; nx*ny*nz hexahedral cells numbered e = ex + nx (ey + ny ez);
+ *  wall-normal vertices y_j = tanh(gamma (2j/ny - 1))/tanh(gamma) (paper
+ *  Sec. 5.1; gamma = 0: uniform).  Reference cell [0,1]^3, nodal tensor basis
+ *  through the Gauss-Lobatto points, node B = i + (k+1)(j + (k+1) m).
+ *  Velocity vector (paper Sec. 3.1, eqs. space/std_fe/enrichment, l = 0):
+ *    [cell][component c=0..2][node B]  followed by the enrichment block
+ *    [enriched cell][component], enriched cells being the wall-adjacent layer
+ *    of each enriched wall, numbered in increasing cell index.
+ *  Pressure vector: [cell][node B] with degree k_p.
+ *  Wall shear stress (tau_w) per wall-face Gauss point of the velocity rule:
+ *    [wall w (0 lower, 1 upper)][ez][ex][qz][qx], nq_u^2 values per face.
+ */
+#ifndef DGWM_H
+#define DGWM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DG_OK = 0,
+  DG_ERR_ARG = -1,            /* invalid argument, size or alignment           */
+  DG_ERR_WORKSPACE = -2,      /* workspace missing or smaller than required    */
+  DG_ERR_HIP = -3,            /* a HIP runtime call failed                     */
+  DG_ERR_NONFINITE = -4,      /* NaN/Inf met in a norm or input                */
+  DG_ERR_NOT_CONVERGED = -5,  /* solver hit its iteration cap                  */
+  DG_ERR_UNSUPPORTED = -6     /* degree/quadrature combination not compiled    */
+};
+
+typedef enum { DG_F64 = 0, DG_F32 = 1 } dg_prec;
+
+typedef struct dg_mesh dg_mesh; /* opaque host handle */
+
+typedef struct {
+  int32_t nx, ny, nz;     /* cells per direction (ny >= 2 when walls exist)               */
+  double Lx, Lz;          /* box lengths in x and z                                      */
+  double gamma;           /* tanh grading of the wall-normal vertices (0 = uniform)      */
+  double wall_amp;        /* amplitude of the cosine lower wall (0 = flat)               */
+  int32_t k_u, k_p;       /* velocity and pressure polynomial degrees                     */
+  int32_t nq_u, nq_p;     /* Gauss points per direction: velocity, pressure               */
+  int32_t nq_wn;          /* wall-normal Gauss points in enriched cells                   */
+  int32_t enrich_lower, enrich_upper; /* enrich the wall-adjacent layer of each wall      */
+  int32_t fully_periodic; /* 1: periodic in y as well, no walls, no enrichment (tests)    */
+  double nu;              /* kinematic viscosity                                         */
+  double kappa, B;        /* Spalding's law constants                                    */
+  double ip_factor_u, ip_factor_p; /* multipliers of the (k+1)^2 |F|/|Omega| penalty      */
+  double wall_ip_mult;    /* extra penalty factor on no-slip faces (paper: 10)            */
+  double theta;           /* adjoint-term sign of the viscous form (+1 symmetric IP)      */
+} dg_mesh_params;
+
+/* ---------------------------------------------------------------- mesh --- */
+
+/* Bytes of device workspace the mesh tables need (>= 0), or a negative
+ * DG_ERR_* code if the parameters are invalid or not compiled in. */
+int64_t dg_mesh_workspace_bytes(const dg_mesh_params* params);
+
+/* Build the mesh on the current device (paper Sec. 3.1-3.2, 5.1):
+ * vertex coordinates, penalties, 1-D basis/quadrature tables, curved-wall
+ * geometry at quadrature points, then the enrichment function psi = U(y+),
+ * y+ = y_h sqrt(tau_w)/nu, and grad psi at every enriched quadrature point by
+ * an FP64 Newton solve of Spalding's law (the law named in Sec. 3.2), and the
+ * diagonal of the Poisson operator.
+ *   tau_w_host: host array in the tau_w layout above (2*nz*nx*nq_u^2 doubles,
+ *               all > 0 and finite), or NULL for tau_w = 1 everywhere.
+ *   workspace:  device buffer of at least dg_mesh_workspace_bytes() bytes; it
+ *               must stay allocated until dg_destroy_mesh.
+ *   out:        receives the handle.  Synchronises `stream` before returning. */
+int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* workspace, size_t ws_bytes,
+                  void* stream, dg_mesh** out);
+
+/* Replace tau_w (device array, tau_w layout, FP64) and recompute psi and grad
+ * psi in FP64 (paper Sec. 3.2: the wall shear stress and with it the
+ * enrichment space are updated once per time step).  Enqueued on `stream`. */
+int dg_update_wall_shear(dg_mesh* mesh, const double* tau_w_dev, void* stream);
+
+/* Number of entries of the velocity (field 0, polynomial + enrichment) or
+ * pressure (field 1) vector; negative on error. */
+int64_t dg_num_dofs(const dg_mesh* mesh, int field);
+
+/* Number of enriched cells. */
+int64_t dg_num_enriched(const dg_mesh* mesh);
+
+void dg_destroy_mesh(dg_mesh* mesh);
+
+/* ----------------------------------------------------------- operators --- */
+
+/* Velocity residual r = R(u) for every test function (paper Sec. 4.2):
+ *   r(phi) = (grad phi, 2 nu eps(u) - u (x) u)_e
+ *          + sum_F ( phi . [ {{u (x) u}} n + Lambda/2 (u- - u+)
+ *                            - {{2 nu eps(u)}} n + tau_F nu (u- - u+) ]
+ *                    - theta nu eps(phi) : ((u- - u+) (x) n) )_F
+ * with the local Lax-Friedrichs Lambda = max(2|u-.n|, 2|u+.n|), mirror data
+ * u+ = -u-, grad u+ = grad u- and tau_F x wall_ip_mult on no-slip walls,
+ * u = u_bar + psi u~ in enriched cells (test functions N_B e_c and psi e_c),
+ * quadrature nq_u^3 (nq_u x nq_wn x nq_u in enriched cells).  M du/dt = -r.
+ *   prec: DG_F64 -> u, r are double*; DG_F32 -> float* (psi tables stay FP64).
+ *   u, r: device vectors of dg_num_dofs(mesh, 0) entries; u != r. */
+int dg_apply_velocity_residual(const dg_mesh* mesh, dg_prec prec, const void* u, void* r, void* stream);
+
+/* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
+ * term, flux eq. ipflux) with homogeneous Neumann data on the walls:
+ *   (A p)(q) = sum_e (grad q, grad p)_e + sum_{interior F} [ -1/2 (grad q.n)(p- - p+)
+ *              - q ({{grad p}}.n - tau_F (p- - p+)) ]_F,
+ * tau_F = ip_factor_p (k_p+1)^2 max(|F|/|Omega-|, |F|/|Omega+|), nq_p^3 Gauss
+ * points.  Flat (box) meshes only.  p, y: device vectors of
+ * dg_num_dofs(mesh, 1) entries of the precision's type; p != y. */
+int dg_apply_poisson(const dg_mesh* mesh, dg_prec prec, const void* p, void* y, void* stream);
+
+/* Diagonal of the Poisson operator (FP64, computed at setup) copied to the
+ * device vector d (dg_num_dofs(mesh, 1) doubles). */
+int dg_poisson_diagonal(const dg_mesh* mesh, double* d, void* stream);
+
+/* ---------------------------------------------------------------- solve --- */
+
+typedef struct {
+  double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 (e.g. 1e-10)           */
+  int32_t max_outer;    /* mixed: iterative-refinement steps; FP64: unused                */
+  int32_t max_inner;    /* mixed: inner FP32 CG iterations per step; FP64: CG iterations  */
+  int32_t cheb_degree;  /* Chebyshev degree of the Jacobi-Chebyshev preconditioner        */
+  double inner_rtol;    /* mixed: relative reduction asked of each inner solve            */
+  int32_t mixed;        /* 1: FP32 inner CG + FP64 refinement; 0: all FP64 CG             */
+} dg_solve_params;
+
+typedef struct {
+  int32_t outer_its, inner_its_total;
+  int32_t op_applies_f64, op_applies_f32;
+  double rel_resid;     /* final ||b - A x|| / ||b|| in FP64                              */
+  double seconds;       /* host wall time of the call                                     */
+} dg_solve_stats;
+
+/* Bytes of device workspace dg_solve_poisson needs. */
+int64_t dg_solve_workspace_bytes(const dg_mesh* mesh, const dg_solve_params* sp);
+
+/* Solve A x = b for the singular SIP Poisson operator (null space: constants).
+ * b is projected to zero mean first (the compatibility condition); x is
+ * returned with zero mean.  x holds the initial guess on entry.  Outer loop in
+ * FP64 (residuals, norms and dot products always FP64, reductions
+ * deterministic); with mixed = 1 the inner Jacobi-Chebyshev preconditioned CG
+ * runs its operator applications in FP32.  Reads back one scalar per outer
+ * iteration (FP64 path: every few iterations) and returns when converged.
+ *   b, x: device double vectors; workspace: dg_solve_workspace_bytes(). */
+int dg_solve_poisson(const dg_mesh* mesh, const dg_solve_params* sp, const double* b, double* x, void* workspace,
+                     size_t ws_bytes, dg_solve_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------- misc --- */
+
+const char* dg_last_error(void);
+
+/* Degree / quadrature combinations compiled into this build, as text. */
+const char* dg_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGWM_H */

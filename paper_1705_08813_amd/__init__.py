@@ -1,0 +1,138 @@
+"""MI355X (gfx950) library for the enriched DG operators of the multiscale
+RANS/LES wall model of Krank, Kronbichler & Wall (arXiv 1705.08813).
+
+The compute path is the HIP shared library libdgwm.so (C ABI in
+include/dgwm.h).  This package holds its Python binding (argument
+marshalling over torch device memory and streams), the seeded input
+generators, and the build script.  Importing the package does not load the
+library; creating a Mesh does, and fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import DG_F32, DG_F64, DgError, SolveParams, SolveStats
+
+__all__ = ["Mesh", "DgError", "DG_F64", "DG_F32", "SolveParams", "SolveStats"]
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """One channel instance resident on the current device.
+
+    cfg: a MeshConfig (paper_1705_08813_amd.inputs) or dict with the fields of
+    dg_mesh_params.  tau_w: host array of wall shear stresses per wall-face
+    Gauss point (layout of include/dgwm.h) or None for tau_w = 1.
+    """
+
+    def __init__(self, cfg, tau_w=None, device=None, stream=None):
+        import numpy as np
+        import torch
+        L = _lib.lib()
+        self.cfg = cfg
+        self.params = _lib.params_from(cfg)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = _lib.check(L.dg_mesh_workspace_bytes(ctypes.byref(self.params)))
+        self.workspace = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        tau_ptr = None
+        if tau_w is not None:
+            self._tau_host = np.ascontiguousarray(tau_w, dtype=np.float64)
+            tau_ptr = self._tau_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(L.dg_setup_mesh(ctypes.byref(self.params), tau_ptr, _dptr(self.workspace), nbytes,
+                                       _stream_ptr(stream), ctypes.byref(handle)))
+        self.handle = handle
+        self.n_vel = int(L.dg_num_dofs(handle, 0))
+        self.n_p = int(L.dg_num_dofs(handle, 1))
+        self.n_enriched = int(L.dg_num_enriched(handle))
+
+    # ------------------------------------------------------------------
+    def _check_vec(self, t, n, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.device != self.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor on {self.device}")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+        if t.dtype not in (torch.float64, torch.float32):
+            raise ValueError(f"{name} must be float64 or float32")
+        return DG_F64 if t.dtype == torch.float64 else DG_F32
+
+    def apply_velocity_residual(self, u, r=None, stream=None):
+        import torch
+        prec = self._check_vec(u, self.n_vel, "u")
+        if r is None:
+            r = torch.empty_like(u)
+        if self._check_vec(r, self.n_vel, "r") != prec:
+            raise ValueError("u and r must have the same dtype")
+        _lib.check(_lib.lib().dg_apply_velocity_residual(self.handle, prec, _dptr(u), _dptr(r), _stream_ptr(stream)))
+        return r
+
+    def apply_poisson(self, p, y=None, stream=None):
+        import torch
+        prec = self._check_vec(p, self.n_p, "p")
+        if y is None:
+            y = torch.empty_like(p)
+        if self._check_vec(y, self.n_p, "y") != prec:
+            raise ValueError("p and y must have the same dtype")
+        _lib.check(_lib.lib().dg_apply_poisson(self.handle, prec, _dptr(p), _dptr(y), _stream_ptr(stream)))
+        return y
+
+    def poisson_diagonal(self, stream=None):
+        import torch
+        d = torch.empty(self.n_p, dtype=torch.float64, device=self.device)
+        _lib.check(_lib.lib().dg_poisson_diagonal(self.handle, _dptr(d), _stream_ptr(stream)))
+        return d
+
+    def update_wall_shear(self, tau_dev, stream=None):
+        import torch
+        if tau_dev.dtype != torch.float64 or tau_dev.device != self.device or not tau_dev.is_contiguous():
+            raise ValueError("tau must be a contiguous float64 tensor on the mesh device")
+        _lib.check(_lib.lib().dg_update_wall_shear(self.handle, _dptr(tau_dev), _stream_ptr(stream)))
+
+    def solve_params(self, rtol=1e-10, mixed=True, max_outer=30, max_inner=200, cheb_degree=5, inner_rtol=1e-4):
+        return SolveParams(rtol=rtol, max_outer=max_outer, max_inner=max_inner, cheb_degree=cheb_degree,
+                           inner_rtol=inner_rtol, mixed=int(mixed))
+
+    def solve_workspace(self, sp):
+        import torch
+        n = _lib.check(_lib.lib().dg_solve_workspace_bytes(self.handle, ctypes.byref(sp)))
+        return torch.empty(max(int(n), 256), dtype=torch.uint8, device=self.device)
+
+    def solve_poisson(self, b, x=None, sp=None, workspace=None, stream=None):
+        import torch
+        if sp is None:
+            sp = self.solve_params()
+        if b.dtype != torch.float64:
+            raise ValueError("b must be float64")
+        self._check_vec(b, self.n_p, "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        self._check_vec(x, self.n_p, "x")
+        if workspace is None:
+            workspace = self.solve_workspace(sp)
+        st = SolveStats()
+        _lib.check(_lib.lib().dg_solve_poisson(self.handle, ctypes.byref(sp), _dptr(b), _dptr(x), _dptr(workspace),
+                                               workspace.numel(), ctypes.byref(st), _stream_ptr(stream)))
+        return x, st
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.lib().dg_destroy_mesh(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,245 @@
+// C ABI entry points: argument checking, mesh set-up on the host, workspace
+// layout, and dispatch to the kernels.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dgwm_internal.h"
+
+namespace dgwm {
+
+namespace {
+thread_local std::string g_err;
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+struct WsLayout {
+  size_t eta, hy, tab_u, tab_p, tau, psi, diag, diag32, total;
+};
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return DG_OK;
+  return set_error(DG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+// Derived sizes; returns an error code for invalid parameters.
+int derive(const dg_mesh_params& P, dg_mesh& m) {
+  if (P.nx < 1 || P.ny < 1 || P.nz < 1) return set_error(DG_ERR_ARG, "cell counts must be >= 1");
+  if (!P.fully_periodic && P.ny < 2) return set_error(DG_ERR_ARG, "ny must be >= 2 when the channel has walls");
+  if (P.k_u < 1 || P.k_u + 1 > kMaxP || P.k_p < 1 || P.k_p + 1 > kMaxP)
+    return set_error(DG_ERR_ARG, "polynomial degree out of range");
+  if (P.nq_u < 1 || P.nq_u > kMaxQ || P.nq_p < 1 || P.nq_p > kMaxQ || P.nq_wn < 1 || P.nq_wn > kMaxQ)
+    return set_error(DG_ERR_ARG, "quadrature size out of range");
+  if (!(P.Lx > 0) || !(P.Lz > 0) || !(P.nu > 0) || !(P.kappa > 0) || !(P.gamma >= 0) ||
+      !std::isfinite(P.Lx + P.Lz + P.nu + P.kappa + P.B + P.gamma + P.wall_amp))
+    return set_error(DG_ERR_ARG, "geometry or material parameter invalid");
+  if (!(P.ip_factor_u > 0) || !(P.ip_factor_p > 0) || !(P.wall_ip_mult > 0))
+    return set_error(DG_ERR_ARG, "penalty factors must be positive");
+  if (P.wall_amp != 0.0) return set_error(DG_ERR_UNSUPPORTED, "curved walls are not supported by this build");
+  m.P = P;
+  m.ncell = (int64_t)P.nx * P.ny * P.nz;
+  m.np_u = P.k_u + 1;
+  m.np_p = P.k_p + 1;
+  m.lower_slot = m.upper_slot = -1;
+  m.n_enr_layers = 0;
+  if (!P.fully_periodic) {
+    if (P.enrich_lower) m.lower_slot = m.n_enr_layers++;
+    if (P.enrich_upper) m.upper_slot = m.n_enr_layers++;
+  }
+  m.nenr = (int64_t)P.nx * P.nz * m.n_enr_layers;
+  m.n_vel = m.ncell * 3 * (int64_t)m.np_u * m.np_u * m.np_u + 3 * m.nenr;
+  m.n_p = m.ncell * (int64_t)m.np_p * m.np_p * m.np_p;
+  m.n_tau = 2 * (int64_t)P.nz * P.nx * P.nq_u * P.nq_u;
+  m.psi_pts = psi_points(P.nq_u, P.nq_wn);
+  m.hx = P.Lx / P.nx;
+  m.hz = P.Lz / P.nz;
+  const int nqw_eff = m.nenr > 0 ? P.nq_wn : -1;
+  if (m.nenr > 0 && !velocity_supported(m.np_u, P.nq_u, nqw_eff))
+    return set_error(DG_ERR_UNSUPPORTED, std::string("velocity (k_u+1, nq_u, nq_wn) not compiled; have ") +
+                                             velocity_combos());
+  if (m.nenr == 0) {
+    bool any = false;
+    for (int w = 1; w <= kMaxQ && !any; ++w) any = velocity_supported(m.np_u, P.nq_u, w);
+    if (!any)
+      return set_error(DG_ERR_UNSUPPORTED, std::string("velocity (k_u+1, nq_u) not compiled; have ") +
+                                               velocity_combos());
+  }
+  if (!poisson_supported(m.np_p, P.nq_p))
+    return set_error(DG_ERR_UNSUPPORTED, std::string("pressure (k_p+1, nq_p) not compiled; have ") +
+                                             poisson_combos());
+  return DG_OK;
+}
+
+WsLayout layout(const dg_mesh& m) {
+  WsLayout L{};
+  size_t o = 0;
+  L.eta = o; o = up256(o + sizeof(double) * (m.P.ny + 1));
+  L.hy = o; o = up256(o + sizeof(double) * m.P.ny);
+  L.tab_u = o;
+  o = up256(o + sizeof(double) * (tab_layout(m.np_u, m.P.nq_u, m.P.nq_wn).size + m.P.nq_u + m.P.nq_wn));
+  L.tab_p = o; o = up256(o + sizeof(double) * tab_layout(m.np_p, m.P.nq_p, m.P.nq_p).size);
+  L.tau = o; o = up256(o + sizeof(double) * m.n_tau);
+  L.psi = o; o = up256(o + sizeof(double) * 4 * (size_t)m.nenr * m.psi_pts);
+  L.diag = o; o = up256(o + sizeof(double) * m.n_p);
+  L.diag32 = o; o = up256(o + sizeof(float) * m.n_p);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+}  // namespace dgwm
+
+using namespace dgwm;
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+const char* dg_build_info(void) {
+  static std::string s;
+  s = std::string("gfx950; ") + velocity_combos() + "; " + poisson_combos();
+  return s.c_str();
+}
+
+int64_t dg_mesh_workspace_bytes(const dg_mesh_params* params) {
+  if (!params) return set_error(DG_ERR_ARG, "params is NULL");
+  dg_mesh m{};
+  int rc = derive(*params, m);
+  if (rc) return rc;
+  return (int64_t)layout(m).total;
+}
+
+int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* workspace, size_t ws_bytes,
+                  void* stream, dg_mesh** out) {
+  if (!params || !out) return set_error(DG_ERR_ARG, "params/out is NULL");
+  *out = nullptr;
+  dg_mesh* m = new dg_mesh();
+  int rc = derive(*params, *m);
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  const WsLayout W = layout(*m);
+  if (!workspace || ws_bytes < W.total) {
+    delete m;
+    return set_error(DG_ERR_WORKSPACE, "mesh workspace missing or too small (need " + std::to_string(W.total) +
+                                           " bytes)");
+  }
+  if (!aligned256(workspace)) {
+    delete m;
+    return set_error(DG_ERR_ARG, "workspace must be 256-byte aligned");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((rc = check_hip(hipGetDevice(&m->device), "hipGetDevice"))) {
+    delete m;
+    return rc;
+  }
+  char* base = static_cast<char*>(workspace);
+  m->eta = reinterpret_cast<double*>(base + W.eta);
+  m->hy = reinterpret_cast<double*>(base + W.hy);
+  m->tab_u = reinterpret_cast<double*>(base + W.tab_u);
+  m->tab_p = reinterpret_cast<double*>(base + W.tab_p);
+  m->tau = reinterpret_cast<double*>(base + W.tau);
+  m->psi = reinterpret_cast<double*>(base + W.psi);
+  m->diag = reinterpret_cast<double*>(base + W.diag);
+  m->diag32 = reinterpret_cast<float*>(base + W.diag32);
+
+  const dg_mesh_params& P = m->P;
+  // wall-normal vertices: tanh grading (paper Sec. 5.1)
+  std::vector<double> eta(P.ny + 1), hy(P.ny);
+  for (int j = 0; j <= P.ny; ++j) {
+    const double t = 2.0 * j / P.ny - 1.0;
+    eta[j] = P.gamma > 0 ? std::tanh(P.gamma * t) / std::tanh(P.gamma) : t;
+  }
+  for (int j = 0; j < P.ny; ++j) hy[j] = eta[j + 1] - eta[j];
+  const TabLayout Lu = tab_layout(m->np_u, P.nq_u, P.nq_wn);
+  std::vector<double> tu(Lu.size + P.nq_u + P.nq_wn), tp(tab_layout(m->np_p, P.nq_p, P.nq_p).size);
+  fill_tables(m->np_u, P.nq_u, P.nq_wn, tu.data());
+  for (int q = 0; q < P.nq_u; ++q) tu[Lu.size + q] = tu[Lu.g + q];
+  for (int q = 0; q < P.nq_wn; ++q) tu[Lu.size + P.nq_u + q] = tu[Lu.gy + q];
+  fill_tables(m->np_p, P.nq_p, P.nq_p, tp.data());
+  std::vector<double> tau(m->n_tau, 1.0);
+  if (tau_w_host) {
+    for (int64_t i = 0; i < m->n_tau; ++i) {
+      if (!(tau_w_host[i] > 0.0) || !std::isfinite(tau_w_host[i])) {
+        delete m;
+        return set_error(DG_ERR_ARG, "tau_w must be positive and finite");
+      }
+      tau[i] = tau_w_host[i];
+    }
+  }
+  rc = check_hip(hipMemcpyAsync(m->eta, eta.data(), sizeof(double) * eta.size(), hipMemcpyHostToDevice, s), "copy");
+  if (!rc) rc = check_hip(hipMemcpyAsync(m->hy, hy.data(), sizeof(double) * hy.size(), hipMemcpyHostToDevice, s), "copy");
+  if (!rc) rc = check_hip(hipMemcpyAsync(m->tab_u, tu.data(), sizeof(double) * tu.size(), hipMemcpyHostToDevice, s), "copy");
+  if (!rc) rc = check_hip(hipMemcpyAsync(m->tab_p, tp.data(), sizeof(double) * tp.size(), hipMemcpyHostToDevice, s), "copy");
+  if (!rc) rc = check_hip(hipMemcpyAsync(m->tau, tau.data(), sizeof(double) * tau.size(), hipMemcpyHostToDevice, s), "copy");
+  if (!rc) rc = launch_psi(m, s);
+  if (!rc) rc = launch_poisson_diag(m, s);
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "setup synchronize");
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return DG_OK;
+}
+
+int dg_update_wall_shear(dg_mesh* m, const double* tau_w_dev, void* stream) {
+  if (!m || !tau_w_dev) return set_error(DG_ERR_ARG, "mesh/tau_w is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = check_hip(hipMemcpyAsync(m->tau, tau_w_dev, sizeof(double) * m->n_tau, hipMemcpyDeviceToDevice, s),
+                     "tau copy");
+  if (rc) return rc;
+  return launch_psi(m, s);
+}
+
+int64_t dg_num_dofs(const dg_mesh* m, int field) {
+  if (!m) return set_error(DG_ERR_ARG, "mesh is NULL");
+  if (field == 0) return m->n_vel;
+  if (field == 1) return m->n_p;
+  return set_error(DG_ERR_ARG, "field must be 0 (velocity) or 1 (pressure)");
+}
+
+int64_t dg_num_enriched(const dg_mesh* m) {
+  if (!m) return set_error(DG_ERR_ARG, "mesh is NULL");
+  return m->nenr;
+}
+
+void dg_destroy_mesh(dg_mesh* m) { delete m; }
+
+int dg_apply_velocity_residual(const dg_mesh* m, dg_prec prec, const void* u, void* r, void* stream) {
+  if (!m || !u || !r) return set_error(DG_ERR_ARG, "mesh/u/r is NULL");
+  if (prec != DG_F64 && prec != DG_F32) return set_error(DG_ERR_ARG, "unknown precision");
+  if (u == r) return set_error(DG_ERR_ARG, "u and r must not alias");
+  if (!aligned256(u) || !aligned256(r)) return set_error(DG_ERR_ARG, "u and r must be 256-byte aligned");
+  return launch_velocity(m, prec, u, r, static_cast<hipStream_t>(stream));
+}
+
+int dg_apply_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, void* stream) {
+  if (!m || !p || !y) return set_error(DG_ERR_ARG, "mesh/p/y is NULL");
+  if (prec != DG_F64 && prec != DG_F32) return set_error(DG_ERR_ARG, "unknown precision");
+  if (p == y) return set_error(DG_ERR_ARG, "p and y must not alias");
+  if (!aligned256(p) || !aligned256(y)) return set_error(DG_ERR_ARG, "p and y must be 256-byte aligned");
+  return launch_poisson(m, prec, p, y, static_cast<hipStream_t>(stream));
+}
+
+int dg_poisson_diagonal(const dg_mesh* m, double* d, void* stream) {
+  if (!m || !d) return set_error(DG_ERR_ARG, "mesh/d is NULL");
+  return check_hip(hipMemcpyAsync(d, m->diag, sizeof(double) * m->n_p, hipMemcpyDeviceToDevice,
+                                  static_cast<hipStream_t>(stream)),
+                   "diagonal copy");
+}
+
+}  // extern "C"

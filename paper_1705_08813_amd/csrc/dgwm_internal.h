@@ -1,0 +1,110 @@
+// Internal declarations of the dgwm library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/dgwm.h"
+
+namespace dgwm {
+
+constexpr int kMaxP = 8;   // nodes per direction (degree <= 7)
+constexpr int kMaxQ = 12;  // Gauss points per direction
+
+// Flat layout of the 1-D tables of one (np, nq, nqy) triple, in doubles.
+// Rule "q" (x and z, and y in regular cells) and rule "y" (wall-normal rule
+// of enriched cells); both tabulate the same nodal basis.
+//   S  [nq][np]  N_i(g_q)          Sd [nq][np]  N_i'(g_q)
+//   D  [nq][nq]  L_r'(g_q), L_r the Lagrange polynomial through the Gauss points
+//   w  [nq]      Gauss weights     g  [nq]      Gauss points (on [0,1])
+//   nd0[np] = N_i'(0), nd1[np] = N_i'(1), gl[np] Gauss-Lobatto nodes,
+//   then S, Sd, D, w, g of the y rule.  Offsets of everything before the y
+//   rule depend on (np, nq) only.
+struct TabLayout {
+  int S, Sd, D, w, g;        // q rule
+  int nd0, nd1, gl;
+  int Sy, Sdy, Dy, wy, gy;   // y rule
+  int size;
+};
+
+__host__ __device__ constexpr TabLayout tab_layout(int np, int nq, int nqy) {
+  TabLayout t{};
+  int o = 0;
+  t.S = o; o += nq * np;
+  t.Sd = o; o += nq * np;
+  t.D = o; o += nq * nq;
+  t.w = o; o += nq;
+  t.g = o; o += nq;
+  t.nd0 = o; o += np;
+  t.nd1 = o; o += np;
+  t.gl = o; o += np;
+  t.Sy = o; o += nqy * np;
+  t.Sdy = o; o += nqy * np;
+  t.Dy = o; o += nqy * nqy;
+  t.wy = o; o += nqy;
+  t.gy = o; o += nqy;
+  t.size = o;
+  return t;
+}
+
+// Points of the enrichment tables of one enriched cell: the volume rule
+// nq x nqy x nq, then the six faces f = 2d + s in order.  Face (d,s) has
+// tangential directions t1 < t2; its points are q1 + Q1 q2 with Q = nqy for
+// the wall-normal direction and nq otherwise.
+__host__ __device__ constexpr int psi_face_points(int nq, int nqy, int d) {
+  return d == 1 ? nq * nq : nq * nqy;
+}
+__host__ __device__ constexpr int psi_face_offset(int nq, int nqy, int f) {
+  int o = nq * nqy * nq;
+  for (int g = 0; g < f; ++g) o += psi_face_points(nq, nqy, g / 2);
+  return o;
+}
+__host__ __device__ constexpr int psi_points(int nq, int nqy) { return psi_face_offset(nq, nqy, 6); }
+
+// Host-side 1-D tables (basis.cpp).
+void fill_tables(int np, int nq, int nqy, double* out);
+void gauss_rule(int n, double* x, double* w);
+void lobatto_nodes(int n, double* x);
+
+}  // namespace dgwm
+
+// Host handle.  All device pointers point into the caller's workspace.
+struct dg_mesh {
+  dg_mesh_params P;
+  int device;
+  int64_t ncell, nenr, n_vel, n_p, n_tau;
+  int np_u, np_p;
+  int n_enr_layers;       // 0, 1 or 2
+  int lower_slot, upper_slot;  // enriched-layer slot of each wall or -1
+  int psi_pts;            // points per enriched cell in the psi tables
+  double hx, hz;
+  // device
+  double* eta;            // ny+1 wall-normal vertex coordinates
+  double* tab_u;          // velocity tables (np_u, nq_u, nq_wn)
+  double* tab_p;          // pressure tables (np_p, nq_p, nq_p)
+  double* tau;            // wall shear stress copy
+  double* psi;            // [enr][psi_pts][4]: psi, dpsi/dx, dpsi/dy, dpsi/dz
+  double* diag;           // Poisson diagonal (FP64)
+  float* diag32;          // Poisson diagonal (FP32 copy)
+  double* hy;             // ny cell heights
+};
+
+namespace dgwm {
+
+// Error reporting (api.hip)
+int set_error(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+// Launchers (defined next to their kernels).  Return DG_OK or an error code.
+int launch_psi(const dg_mesh* m, hipStream_t s);
+int launch_poisson_diag(const dg_mesh* m, hipStream_t s);
+int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s);
+int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+bool poisson_supported(int np, int nq);
+bool velocity_supported(int np, int nq, int nqy);
+const char* velocity_combos();
+const char* poisson_combos();
+
+}  // namespace dgwm

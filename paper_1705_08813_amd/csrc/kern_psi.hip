@@ -1,0 +1,135 @@
+// Enrichment function psi and its gradient at every quadrature point of the
+// enriched cells (arXiv 1705.08813, Sec. 3.2), FP64.
+//
+//   y+ = y_h sqrt(tau_w) / nu    (rho = 1)
+//   psi = U(y+) with U the root of Spalding's law
+//         y+ = U + exp(-kappa B) (exp(kappa U) - 1 - kappa U - (kappa U)^2/2 - (kappa U)^3/6)
+//   grad psi = U'(y+) sqrt(tau_w)/nu grad y_h
+//
+// y_h is the wall distance (flat walls: exact, since the linear interpolation
+// of the vertex distances is exact there).  tau_w is the value of the
+// wall-face Gauss column nearest to the point (piecewise constant over the
+// cell's wall footprint, zero gradient).  The tables are computed once per
+// wall-shear update and stored, as the paper does for its enrichment.
+#include "kern_common.h"
+
+namespace dgwm {
+
+namespace {
+
+// Safeguarded Newton for Spalding's law.  f(U) is increasing and convex on
+// U >= 0 with f(0) = -y+ <= 0 <= f(y+), so [0, y+] brackets the root; steps
+// leaving the bracket fall back to bisection.
+__device__ void spalding_root(double yp, double kappa, double B, double& U, double& dU) {
+  const double c = exp(-kappa * B);
+  double lo = 0.0, hi = yp;
+  double x = yp < 10.0 ? yp : fmin(yp, log(yp) / kappa + B);
+  for (int it = 0; it < 100; ++it) {
+    const double k = kappa * x;
+    const double em1 = expm1(k);
+    const double f = x + c * (em1 - k - 0.5 * k * k - k * k * k / 6.0) - yp;
+    if (f == 0.0) break;
+    if (f > 0.0) hi = x; else lo = x;
+    const double df = 1.0 + c * kappa * (em1 - k - 0.5 * k * k);
+    double xn = x - f / df;
+    if (!(xn >= lo && xn <= hi)) xn = 0.5 * (lo + hi);
+    const double step = fabs(xn - x);
+    x = xn;
+    if (step <= 4e-16 * fmax(1.0, x)) break;
+  }
+  const double k = kappa * x;
+  U = x;
+  dU = 1.0 / (1.0 + c * kappa * (expm1(k) - k - 0.5 * k * k));
+}
+
+// pts: the NQ Gauss points of the wall-parallel rule followed by the NQY
+// points of the wall-normal rule (on [0,1]).
+template <int NQ, int NQY>
+__global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, const double* __restrict__ eta,
+                           const double* __restrict__ pts, const double* __restrict__ tau, double nu, double kappa,
+                           double B, int64_t nenr, int psi_pts, double* __restrict__ psi) {
+  constexpr int NPTS = NQ * NQY * NQ;
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= nenr * psi_pts) return;
+  const int64_t enr = gid / psi_pts;
+  const int pt = (int)(gid - enr * psi_pts);
+  const int ex = (int)(enr % nx);
+  const int64_t t0 = enr / nx;
+  const int slot = (int)(t0 % nslots);
+  const int ez = (int)(t0 / nslots);
+  const bool lower = (slot == lower_slot);
+  const int ey = lower ? 0 : ny - 1;
+  const double* gy = pts + NQ;
+  // wall-normal reference coordinate of the point and its tau column
+  double xiy;
+  int qx, qz;
+  if (pt < NPTS) {
+    qx = pt % NQ;
+    xiy = gy[(pt / NQ) % NQY];
+    qz = pt / (NQ * NQY);
+  } else {
+    int f = 0, o = NPTS;
+    while (pt >= o + psi_face_points(NQ, NQY, f / 2)) {
+      o += psi_face_points(NQ, NQY, f / 2);
+      ++f;
+    }
+    const int d = f / 2, s = f % 2, k = pt - o;
+    const int Q1 = d == 0 ? NQY : NQ;  // first tangential direction: y for x-faces, x otherwise
+    const int q1 = k % Q1, q2 = k / Q1;
+    if (d == 0) {
+      qx = s ? NQ - 1 : 0;
+      xiy = gy[q1];
+      qz = q2;
+    } else if (d == 1) {
+      qx = q1;
+      xiy = (double)s;
+      qz = q2;
+    } else {
+      qx = q1;
+      xiy = gy[q2];
+      qz = s ? NQ - 1 : 0;
+    }
+  }
+  const double y = eta[ey] + (eta[ey + 1] - eta[ey]) * xiy;
+  const double yh = lower ? y + 1.0 : 1.0 - y;
+  const double dyh = lower ? 1.0 : -1.0;
+  const int w = lower ? 0 : 1;
+  const double tw = tau[(((int64_t)w * nz + ez) * nx + ex) * NQ * NQ + (int64_t)qz * NQ + qx];
+  double* o = psi + gid * 4;
+  if (!(tw > 0.0) || !isfinite(tw)) {
+    o[0] = o[1] = o[2] = o[3] = __builtin_nan("");
+    return;
+  }
+  const double st = sqrt(tw) / nu;
+  double U, dU;
+  spalding_root(fmax(yh, 0.0) * st, kappa, B, U, dU);
+  o[0] = U;
+  o[1] = 0.0;
+  o[2] = dU * st * dyh;
+  o[3] = 0.0;
+}
+
+}  // namespace
+
+#define DG_PSI_COMBOS(X) X(4, 8) X(4, 4) X(5, 8) X(5, 5) X(7, 8) X(8, 8)
+
+int launch_psi(const dg_mesh* m, hipStream_t s) {
+  if (m->nenr == 0) return DG_OK;
+  // the Gauss points of both rules, contiguous, right after the tables
+  const double* pts = m->tab_u + tab_layout(m->np_u, m->P.nq_u, m->P.nq_wn).size;
+  const int64_t n = m->nenr * m->psi_pts;
+  const unsigned nb = (unsigned)((n + 127) / 128);
+  const int lower_slot = m->lower_slot;
+#define X(a, b)                                                                                              \
+  if (m->P.nq_u == a && m->P.nq_wn == b) {                                                                   \
+    hipLaunchKernelGGL((psi_kernel<a, b>), dim3(nb), dim3(128), 0, s, m->P.nx, m->P.ny, m->P.nz, lower_slot, \
+                       m->n_enr_layers, m->eta, pts, m->tau, m->P.nu, m->P.kappa, m->P.B, m->nenr,          \
+                       m->psi_pts, m->psi);                                                                  \
+    return check_hip(hipGetLastError(), "psi kernel launch");                                                \
+  }
+  DG_PSI_COMBOS(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "psi table: quadrature combination not compiled");
+}
+
+}  // namespace dgwm

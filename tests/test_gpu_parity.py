@@ -1,0 +1,192 @@
+"""GPU parity of the HIP operators against the FP64 CPU oracle, through the C ABI.
+
+FP64: ||r_gpu - r_oracle||_inf <= 1e-12 ||r_oracle||_inf, checked separately
+on the polynomial block and on the enrichment block of the velocity residual.
+FP32: elementwise |r32 - r| <= c_m u32 R_abs + tiny, with R_abs the oracle
+evaluated with absolute values of every factor (a bound on the magnitude of
+every summand), u32 = 2^-24, and c_m = 4 (3 (nq + k + 1) + 40) covering the
+longest accumulation chain of the sum-factorized evaluation (interpolation,
+collocation derivative, transposed sweeps, six faces); inputs are the FP32
+roundings, fed to the oracle as well.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1705_08813_amd import Mesh
+from paper_1705_08813_amd.inputs import PRESETS, MeshConfig, Workload, draw_inputs
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _split(cfg, r):
+    n = cfg.ncell * 3 * (cfg.k_u + 1) ** 3
+    return r[:n], r[n:]
+
+
+VEL_CASES = {
+    "tiny": PRESETS["tiny"],
+    "k2_stretched": Workload("k2", MeshConfig(nx=3, ny=4, nz=2, gamma=1.3, k_u=2, nq_u=4, k_p=1, nq_p=2), 11, 0.5, 1.5),
+    "k4_large_like": Workload("k4", MeshConfig(nx=5, ny=4, nz=3, gamma=1.8, k_u=4, nq_u=7), 12, 0.5, 1.5),
+    "k5_curved_rule": Workload("k5", MeshConfig(nx=2, ny=3, nz=2, gamma=0.7, k_u=5, nq_u=8, k_p=4, nq_p=5), 13, 0.2, 2.0),
+    "k3_periodic": Workload("k3p", MeshConfig(nx=3, ny=3, nz=2, k_u=3, nq_u=5, nq_wn=8, fully_periodic=1), 14, 1, 1),
+    "k4_lower_only": Workload("k4l", MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=4, nq_u=7, enrich_upper=0), 15, 0.5, 1.5),
+    "k3_nonsym": Workload("k3n", MeshConfig(nx=2, ny=3, nz=3, gamma=0.9, k_u=3, nq_u=5, theta=-1.0), 16, 0.5, 1.5),
+    "k3_self_periodic": Workload("k3s", MeshConfig(nx=1, ny=2, nz=1, k_u=3, nq_u=4, nq_wn=8), 17, 0.5, 1.5),
+}
+
+
+@pytest.mark.parametrize("name", list(VEL_CASES))
+def test_velocity_residual_f64(name):
+    wl = VEL_CASES[name]
+    _log(f"[gpu] velocity f64 case={name}")
+    inp = draw_inputs(wl)
+    r_orc = O.velocity_residual(wl.mesh, inp["u"], inp["tau"])
+    mesh = Mesh(wl.mesh, inp["tau"])
+    r = mesh.apply_velocity_residual(torch.tensor(inp["u"], device="cuda"))
+    torch.cuda.synchronize()
+    r = r.cpu().numpy()
+    rp, re = _split(wl.mesh, r)
+    op, oe = _split(wl.mesh, r_orc)
+    assert _rel(rp, op) <= 1e-12, _rel(rp, op)
+    if oe.size:
+        assert _rel(re, oe) <= 1e-12, _rel(re, oe)
+
+
+@pytest.mark.parametrize("name", ["tiny", "k4_large_like", "k3_periodic"])
+def test_velocity_residual_f32_bound(name):
+    wl = VEL_CASES[name]
+    _log(f"[gpu] velocity f32 case={name}")
+    inp = draw_inputs(wl)
+    u32 = inp["u"].astype(np.float32)
+    u_r = u32.astype(np.float64)
+    r_orc = O.velocity_residual(wl.mesh, u_r, inp["tau"])
+    r_abs = O.velocity_residual(wl.mesh, u_r, inp["tau"], absmode=True)
+    mesh = Mesh(wl.mesh, inp["tau"])
+    r = mesh.apply_velocity_residual(torch.tensor(u32, device="cuda")).cpu().numpy().astype(np.float64)
+    m = 3 * (wl.mesh.nq_u + wl.mesh.k_u + 1) + 40
+    bound = 4 * m * U32 * r_abs + 1e-30
+    err = np.abs(r - r_orc)
+    worst = float((err / bound).max())
+    _log(f"[gpu]   max rel err {_rel(r, r_orc):.3e}, max err/bound {worst:.3f}")
+    assert worst <= 1.0
+
+
+POI_CASES = {
+    "tiny": PRESETS["tiny"].mesh,
+    "k1": MeshConfig(nx=3, ny=4, nz=2, gamma=1.3, k_p=1, nq_p=2),
+    "k3_stretched": MeshConfig(nx=4, ny=5, nz=3, gamma=1.8, k_p=3, nq_p=4),
+    "k4": MeshConfig(nx=2, ny=3, nz=2, gamma=0.5, k_p=4, nq_p=5, k_u=5, nq_u=8),
+    "k5": MeshConfig(nx=2, ny=2, nz=2, k_p=5, nq_p=6, k_u=5, nq_u=8),
+    "k2_periodic": MeshConfig(nx=3, ny=3, nz=3, k_p=2, nq_p=3, k_u=3, nq_u=5, fully_periodic=1),
+    "k3_self_periodic": MeshConfig(nx=1, ny=3, nz=1, gamma=1.0, k_p=3, nq_p=4, k_u=3, nq_u=4, nq_wn=8),
+}
+
+
+@pytest.mark.parametrize("name", list(POI_CASES))
+def test_poisson_f64_and_diagonal(name):
+    cfg = POI_CASES[name]
+    _log(f"[gpu] poisson f64 case={name}")
+    p = np.random.default_rng(21).uniform(-1, 1, cfg.n_p)
+    y_orc = O.poisson_apply(cfg, p)
+    mesh = Mesh(cfg)
+    y = mesh.apply_poisson(torch.tensor(p, device="cuda"))
+    d = mesh.poisson_diagonal()
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), y_orc) <= 1e-12
+    assert _rel(d.cpu().numpy(), O.poisson_diag(cfg)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny", "k3_stretched", "k2_periodic"])
+def test_poisson_f32_bound(name):
+    cfg = POI_CASES[name]
+    _log(f"[gpu] poisson f32 case={name}")
+    p32 = np.random.default_rng(22).uniform(-1, 1, cfg.n_p).astype(np.float32)
+    pr = p32.astype(np.float64)
+    y_orc = O.poisson_apply(cfg, pr)
+    y_abs = O.poisson_apply(cfg, pr, absmode=True)
+    mesh = Mesh(cfg)
+    y = mesh.apply_poisson(torch.tensor(p32, device="cuda")).cpu().numpy().astype(np.float64)
+    m = 3 * (cfg.nq_p + cfg.k_p + 1) + 40
+    worst = float((np.abs(y - y_orc) / (4 * m * U32 * y_abs + 1e-30)).max())
+    _log(f"[gpu]   max rel err {_rel(y, y_orc):.3e}, max err/bound {worst:.3f}")
+    assert worst <= 1.0
+
+
+def test_large_config_poisson_full_and_velocity_sampled():
+    """64x32x32, tanh 1.8, k=4 / k=3, in the configuration the benchmark times:
+    the whole Poisson output against the oracle, and the velocity residual on
+    a sample of cells (both enriched layers, their neighbours, interior)."""
+    wl = PRESETS["large"]
+    m = wl.mesh
+    _log("[gpu] large config: setup")
+    inp = draw_inputs(wl)
+    mesh = Mesh(m, inp["tau"])
+    _log("[gpu] large config: poisson f64")
+    y = mesh.apply_poisson(torch.tensor(inp["p"], device="cuda"))
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), O.poisson_apply(m, inp["p"])) <= 1e-12
+    _log("[gpu] large config: velocity f64")
+    u = torch.tensor(inp["u"], device="cuda")
+    r = mesh.apply_velocity_residual(u).cpu().numpy()
+    rng = np.random.default_rng(5)
+    nx, ny, nz = m.nx, m.ny, m.nz
+    cells = set(rng.integers(0, m.ncell, 200).tolist())
+    for ey in (0, 1, ny - 2, ny - 1):
+        for _ in range(40):
+            cells.add(int(rng.integers(0, nx)) + nx * (ey + ny * int(rng.integers(0, nz))))
+    cells |= {0, nx - 1, m.ncell - 1}
+    cells = np.array(sorted(cells), dtype=np.int64)
+    r_orc = O.velocity_residual(m, inp["u"], inp["tau"], cells=cells)
+    n3 = (m.k_u + 1) ** 3
+    rows = (cells[:, None] * 3 * n3 + np.arange(3 * n3)[None, :]).ravel()
+    assert _rel(r[rows], r_orc[rows]) <= 1e-12
+    # enrichment rows of the sampled enriched cells
+    off = m.ncell * 3 * n3
+    enr_rows = []
+    for e in cells:
+        ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+        if ey in (0, ny - 1):
+            slot = 0 if ey == 0 else 1
+            k = ex + nx * (slot + 2 * ez)
+            enr_rows += [off + 3 * k + c for c in range(3)]
+    enr_rows = np.array(enr_rows)
+    assert _rel(r[enr_rows], r_orc[enr_rows]) <= 1e-12
+
+
+def test_repeat_applies_are_bitwise_identical():
+    """Deterministic: no atomics, fixed reduction order."""
+    wl = PRESETS["tiny"]
+    inp = draw_inputs(wl)
+    mesh = Mesh(wl.mesh, inp["tau"])
+    u = torch.tensor(inp["u"], device="cuda")
+    p = torch.tensor(inp["p"], device="cuda")
+    r1 = mesh.apply_velocity_residual(u).clone()
+    r2 = mesh.apply_velocity_residual(u)
+    y1 = mesh.apply_poisson(p).clone()
+    y2 = mesh.apply_poisson(p)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r2) and torch.equal(y1, y2)
+
+
+def test_wall_shear_update_matches_fresh_setup():
+    wl = VEL_CASES["k4_lower_only"]
+    inp = draw_inputs(wl)
+    tau2 = np.random.default_rng(99).uniform(0.3, 2.0, wl.mesh.n_tau)
+    mesh = Mesh(wl.mesh, inp["tau"])
+    mesh.update_wall_shear(torch.tensor(tau2, device="cuda"))
+    u = torch.tensor(inp["u"], device="cuda")
+    r = mesh.apply_velocity_residual(u).cpu().numpy()
+    r_orc = O.velocity_residual(wl.mesh, inp["u"], tau2)
+    assert _rel(r, r_orc) <= 1e-12
