@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the enriched DG hot path on one MI355X.
+
+One step = one pass of the operator hot path over the 64x32x32 channel
+(tanh grading 1.8, k=4 velocity with the 7-point rule and 7x8x7 points in
+the two enriched wall layers, k=3 pressure), all in FP64:
+  1. wall-shear update: psi and grad psi by the FP64 Spalding Newton solve,
+  2. enriched velocity residual (LLF convective + SIP viscous),
+  3. SIP Poisson operator.
+value = (velocity DoFs + pressure DoFs) per step / seconds per step.
+
+Inputs are resident in HBM before the timed region.  Per-operator times
+come from HIP events recorded on the stream the library launches on.  The
+CPU oracle is timed on a bounded sample of the same workload (rank 0).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DG operator DoFs/s (FP64 vs FP32-mixed) at 1e-10 resid; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VEC_TFLOPS = 78.6         # MI355X FP64 vector peak
+FP32_VEC_TFLOPS = 157.3
+# Algorithmic work of the k=4 velocity residual with the 7-point rule:
+# sum-factorized interpolation + collocation gradients + transposed sweeps for
+# three components plus the face terms, without even-odd splitting:
+# about 766 flop per velocity DoF.  Memory: read u, write r = 16 B/DoF (FP64).
+VEL_FLOP_PER_DOF = 766.0
+BYTES_PER_DOF_F64 = 16.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("kern_velocity.hip", "kern_common.h", "kern_poisson.hip"):
+        with open(os.path.join(ROOT, "paper_1705_08813_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(n_launch_units):
+    """HBM bytes per velocity-residual launch measured with rocprofv3 PMC
+    counters (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    or None if missing or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_velocity_large.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_src_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, inp):
+    """The oracle as it stands, on 4 z-slabs of the same mesh (8192 cells,
+    both enriched layers included): velocity residual + Poisson apply."""
+    import numpy as np
+    import oracle as O
+    m = wl.mesh
+    nslab = 4
+    cells = np.arange(nslab * m.nx * m.ny, dtype=np.int64)
+    n_enr_in = nslab * m.nx * 2
+    dofs = cells.size * 3 * (m.k_u + 1) ** 3 + 3 * n_enr_in + cells.size * (m.k_p + 1) ** 3
+    O.lib()
+    t0 = time.perf_counter()
+    O.velocity_residual(m, inp["u"], inp["tau"], cells=cells)
+    t1 = time.perf_counter()
+    O.poisson_apply(m, inp["p"], cells=cells)
+    t2 = time.perf_counter()
+    return {"value": dofs / (t2 - t0), "unit": "DoFs/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{cells.size} of {m.ncell} cells (z-slabs 0-{nslab - 1}): velocity residual "
+                      f"{t1 - t0:.2f} s + Poisson apply {t2 - t1:.2f} s, {dofs} DoFs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for PMC byte calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of the path is described, not built.", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1705_08813_amd import Mesh
+    from paper_1705_08813_amd.inputs import PRESETS, draw_inputs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = PRESETS["large"]
+    m = wl.mesh
+    inp = draw_inputs(wl)
+    mesh = Mesh(m, inp["tau"], device=dev)
+    u = torch.tensor(inp["u"], device=dev)
+    p = torch.tensor(inp["p"], device=dev)
+    tau = torch.tensor(inp["tau"], device=dev)
+    r = torch.empty_like(u)
+    y = torch.empty_like(p)
+    stream = torch.cuda.current_stream()
+    n_vel, n_p = mesh.n_vel, mesh.n_p
+
+    def step():
+        mesh.update_wall_shear(tau)
+        mesh.apply_velocity_residual(u, r)
+        mesh.apply_poisson(p, y)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        e = ev[k]
+        e[0].record(stream)
+        mesh.update_wall_shear(tau)
+        e[1].record(stream)
+        mesh.apply_velocity_residual(u, r)
+        e[2].record(stream)
+        mesh.apply_poisson(p, y)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_psi = sum(e[0].elapsed_time(e[1]) for e in ev) / K * 1e-3
+    t_vel = sum(e[1].elapsed_time(e[2]) for e in ev) / K * 1e-3
+    t_poi = sum(e[2].elapsed_time(e[3]) for e in ev) / K * 1e-3
+    dofs_step = n_vel + n_p
+    value = dofs_step * K / wall
+
+    vel_flops = VEL_FLOP_PER_DOF * n_vel
+    ach_tflops = vel_flops / t_vel / 1e12
+    traffic = load_traffic(n_vel)
+    roofline = {"bound": "alu", "achieved": round(ach_tflops, 3), "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach_tflops / FP64_VEC_TFLOPS, 4), "traffic": traffic,
+                "kernel": "velocity residual (vel_kernel regular + enriched launches), FP64",
+                "per_launch_ms": round(t_vel * 1e3, 4), "algorithmic_flop_per_dof": VEL_FLOP_PER_DOF}
+    out = {"metric": METRIC, "value": value, "unit": "DoFs/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+           "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "channel 64x32x32, tanh 1.8, k_u=4 (7^3 Gauss points, 7x8x7 in 4096 enriched "
+                                  "wall cells), k_p=3 (4^3), FP64: psi refresh + velocity residual + SIP Poisson",
+                      "velocity_dofs": n_vel, "pressure_dofs": n_p, "seed": wl.seed},
+           "roofline": roofline}
+    extras = {"psi_ms": t_psi * 1e3, "velocity_ms": t_vel * 1e3, "poisson_ms": t_poi * 1e3,
+              "velocity_GBps_alg": BYTES_PER_DOF_F64 * n_vel / t_vel / 1e9,
+              "poisson_GBps_alg": BYTES_PER_DOF_F64 * n_p / t_poi / 1e9,
+              "velocity_hbm_frac_alg": BYTES_PER_DOF_F64 * n_vel / t_vel / 1e9 / HBM_PEAK_GBS,
+              "poisson_hbm_frac_alg": BYTES_PER_DOF_F64 * n_p / t_poi / 1e9 / HBM_PEAK_GBS,
+              "kernel_src_sha": kernel_source_hash()}
+
+    if not args.no_extras:
+        # FP32 operator applications on the same data
+        u32, p32 = u.float(), p.float()
+        r32, y32 = torch.empty_like(u32), torch.empty_like(p32)
+        for _ in range(3):
+            mesh.apply_velocity_residual(u32, r32)
+            mesh.apply_poisson(p32, y32)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        n32 = max(5, K // 2)
+        e0.record(stream)
+        for _ in range(n32):
+            mesh.apply_velocity_residual(u32, r32)
+        e1.record(stream)
+        for _ in range(n32):
+            mesh.apply_poisson(p32, y32)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        tv32 = e0.elapsed_time(e1) / n32 * 1e-3
+        tp32 = e1.elapsed_time(e2) / n32 * 1e-3
+        extras.update({"velocity_f32_ms": tv32 * 1e3, "poisson_f32_ms": tp32 * 1e3,
+                       "f32_step_dofs_per_s": dofs_step / (tv32 + tp32),
+                       "velocity_f32_GBps_alg": 8.0 * n_vel / tv32 / 1e9,
+                       "poisson_f32_GBps_alg": 8.0 * n_p / tp32 / 1e9})
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)  # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        extras["copy_calibration_bytes"] = a.numel()
+    out["extras"] = extras
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, inp)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,8 +65,15 @@ def lib():
         L.orc_poisson_diag.argtypes = [P, _I64, ctypes.c_int64, _D]
         L.orc_psi_point.argtypes = [P, _D, ctypes.c_int64, _D, _D]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         _LIB = L
     return _LIB
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle runs on."""
+    return int(lib().orc_num_threads())
 
 
 def params(cfg) -> OrcParams:

@@ -40,6 +40,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_MAXN 16
 
@@ -871,4 +872,15 @@ int orc_cell_map(const orc_params *P, int64_t e, const double *xi, double *X, do
   *detJ = inv3(J, Ji);
   ctx_free(&C);
   return 0;
+}
+
+/* Number of OpenMP threads the oracle uses (for reporting). */
+int orc_num_threads(void) {
+  int n = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+  return n;
 }
