@@ -143,12 +143,12 @@ int dg_poisson_diagonal(const dg_mesh* mesh, double* d, void* stream);
 /* ---------------------------------------------------------------- solve --- */
 
 typedef struct {
-  double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 (e.g. 1e-10)           */
-  int32_t max_outer;    /* mixed: iterative-refinement steps; FP64: unused                */
-  int32_t max_inner;    /* mixed: inner FP32 CG iterations per step; FP64: CG iterations  */
-  int32_t cheb_degree;  /* Chebyshev degree of the Jacobi-Chebyshev preconditioner        */
-  double inner_rtol;    /* mixed: relative reduction asked of each inner solve            */
-  int32_t mixed;        /* 1: FP32 inner CG + FP64 refinement; 0: all FP64 CG             */
+  double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2 (e.g. 1e-10), true residual  */
+  int32_t max_outer;    /* cap on the FP64 (outer) conjugate-gradient iterations                */
+  int32_t max_inner;    /* mixed: FP32 CG iterations per preconditioner call (0: polynomial only)*/
+  int32_t cheb_degree;  /* degree of the Jacobi-Chebyshev polynomial preconditioner (>= 1)      */
+  double inner_rtol;    /* reserved (inner iterations run a fixed count, without host syncs)   */
+  int32_t mixed;        /* 1: preconditioner in FP32; 0: everything FP64                        */
 } dg_solve_params;
 
 typedef struct {
@@ -161,14 +161,21 @@ typedef struct {
 /* Bytes of device workspace dg_solve_poisson needs. */
 int64_t dg_solve_workspace_bytes(const dg_mesh* mesh, const dg_solve_params* sp);
 
-/* Solve A x = b for the singular SIP Poisson operator (null space: constants).
+/* Solve A x = b for the singular SIP Poisson operator (null space: constants;
+ * the pressure equation of the paper's dual-splitting step, Sec. 4.1-4.2).
  * b is projected to zero mean first (the compatibility condition); x is
- * returned with zero mean.  x holds the initial guess on entry.  Outer loop in
- * FP64 (residuals, norms and dot products always FP64, reductions
- * deterministic); with mixed = 1 the inner Jacobi-Chebyshev preconditioned CG
- * runs its operator applications in FP32.  Reads back one scalar per outer
- * iteration (FP64 path: every few iterations) and returns when converged.
- *   b, x: device double vectors; workspace: dg_solve_workspace_bytes(). */
+ * returned with zero mean.  x holds the initial guess on entry.
+ * Outer loop: flexible preconditioned CG in FP64 (residuals, norms and dot
+ * products always FP64, deterministic fixed-order reductions, true residual
+ * recomputed periodically and before convergence is accepted).
+ * Preconditioner: Chebyshev polynomial of degree cheb_degree in D^{-1} A on
+ * [lmax/30, 1.1 lmax] (lmax from 20 Lanczos steps, cached in the mesh); with
+ * mixed = 1 its operator applications run in FP32 on the normalised
+ * residual, optionally wrapped in max_inner FP32 CG iterations.
+ * Reads back one scalar per outer iteration and returns when converged.
+ *   b, x: device double vectors; workspace: dg_solve_workspace_bytes().
+ *   Errors: DG_ERR_NOT_CONVERGED (stats filled) after max_outer iterations,
+ *   DG_ERR_NONFINITE on NaN/Inf. */
 int dg_solve_poisson(const dg_mesh* mesh, const dg_solve_params* sp, const double* b, double* x, void* workspace,
                      size_t ws_bytes, dg_solve_stats* stats, void* stream);
 

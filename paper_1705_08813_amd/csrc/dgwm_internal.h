@@ -89,6 +89,7 @@ struct dg_mesh {
   double* diag;           // Poisson diagonal (FP64)
   float* diag32;          // Poisson diagonal (FP32 copy)
   double* hy;             // ny cell heights
+  double lam_max = 0.0;   // cached largest eigenvalue estimate of D^{-1} A (solver)
 };
 
 namespace dgwm {

@@ -23,20 +23,104 @@ struct VelShape {
   static constexpr int NP2 = NP * NP, NP3 = NP * NP * NP;
   static constexpr int NPTS = NQ * NQY * NQ;
   static constexpr int FMAX = (NQ * NQY > NQ * NQ) ? NQ * NQY : NQ * NQ;
-  static constexpr int LAY = 2 * 3 * 2 * NP2;   // [side][c][value|normal derivative][NP2]
-  static constexpr int TR = 2 * 3 * 4 * FMAX;   // [side][c][val|d_t1|d_t2|d_n][FMAX]
-  static constexpr int FL = 12 * FMAX;          // [fv c | Fg c k][FMAX]
-  static constexpr int FACE = LAY + TR + FL;
+  static constexpr int Q1MAX = NQY > NQ ? NQY : NQ;
+  static constexpr int NL = 6 * 3 * 2 * NP2;            // neighbour layers [face][c][val|d_n][NP2]
+  static constexpr int LAYO = 2 * 3 * 2 * NP2;          // own layers of the two faces of one direction
+  static constexpr int A1 = 2 * 2 * 3 * 3 * Q1MAX * NP; // t1-swept traces [s][side][c][field][q1][i2]
+  static constexpr int FL = 2 * 12 * FMAX;              // fluxes [s][fv c | Fg c k][pt]
+  static constexpr int B1 = 2 * 3 * 3 * Q1MAX * NP;     // t2-transposed tests [s][c][3][q1][i2]
+  static constexpr int FACE = NL + LAYO + A1 + FL + B1;
   static constexpr int VOL = 12 * NPTS;
   static constexpr int BIG = VOL > FACE ? VOL : FACE;
 };
 
-// Processes face (D, S) of the current cell.  T1 < T2 are the tangential
-// directions.  Adds the integrated flux to s_r and (enriched cells) to rt.
-template <typename T, int NP, int NQ, int NQY, bool ENR, int D, int S>
-__device__ __forceinline__ void vel_face(const MeshDev& M, const T* __restrict__ u, const T* s_u, T* s_r,
-                                         T* s_big, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
-                                         T hy, T hz, T rt[3]) {
+// Node index of the point at position l along direction D on the line
+// (a, b) of the two tangential directions (t1 < t2):  base + l * stride.
+template <int NP>
+__device__ __forceinline__ void line_of(int D, int a, int b, int& base, int& stride) {
+  if (D == 0) {
+    base = NP * (a + NP * b);
+    stride = 1;
+  } else if (D == 1) {
+    base = a + NP * NP * b;
+    stride = NP;
+  } else {
+    base = a + NP * b;
+    stride = NP * NP;
+  }
+}
+
+// Neighbour of the current cell across face (D, S).
+struct FaceNb {
+  int64_t enb;     // neighbour cell (valid unless wall)
+  int64_t enr_nb;  // its enriched index or -1
+  bool wall;
+  int nidx1;       // neighbour's ey (for its height)
+};
+
+__device__ __forceinline__ FaceNb face_nb(const MeshDev& M, int ex, int ey, int ez, int D, int S) {
+  int n[3] = {ex, ey, ez};
+  const int nmax = D == 0 ? M.nx : (D == 1 ? M.ny : M.nz);
+  int j = (D == 0 ? ex : (D == 1 ? ey : ez)) + (S ? 1 : -1);
+  FaceNb f;
+  f.wall = false;
+  if (j < 0 || j >= nmax) {
+    if (D == 1 && !M.fully_periodic) f.wall = true;
+    j = (j + nmax) % nmax;
+  }
+  n[D] = j;
+  f.enb = n[0] + (int64_t)M.nx * (n[1] + (int64_t)M.ny * n[2]);
+  f.enr_nb = f.wall ? -1 : enr_index(M, n[0], n[1], n[2]);
+  f.nidx1 = n[1];
+  return f;
+}
+
+// Neighbour face layers of all six faces: value and normal derivative of each
+// component on the neighbour's node layer at the shared face.  One global
+// read per neighbour node; all six faces are fetched in one phase.
+template <typename T, int NP>
+__device__ __forceinline__ void load_neighbour_layers(const MeshDev& M, const T* __restrict__ u, T* s_nl, T* s_nut,
+                                                      const double* tab_nd0, const double* tab_nd1, int ex, int ey,
+                                                      int ez, bool need_nut) {
+  constexpr int NP2 = NP * NP, NP3 = NP * NP * NP;
+  for (int t = threadIdx.x; t < 6 * 3 * NP2; t += blockDim.x) {
+    const int f = t / (3 * NP2), rem = t - f * 3 * NP2;
+    const int c = rem / NP2, k = rem - c * NP2;
+    const int D = f >> 1, S = f & 1;
+    const FaceNb nb = face_nb(M, ex, ey, ez, D, S);
+    T val = 0, der = 0;
+    if (!nb.wall) {
+      int base, stride;
+      line_of<NP>(D, k % NP, k / NP, base, stride);
+      const double* nd = S ? tab_nd0 : tab_nd1;  // neighbour's face is at xi_D = 1 - S
+      const int lface = S ? 0 : NP - 1;
+      const T* src = u + (nb.enb * 3 + c) * NP3 + base;
+      T x[NP];
+#pragma unroll
+      for (int l = 0; l < NP; ++l) x[l] = src[l * stride];
+#pragma unroll
+      for (int l = 0; l < NP; ++l) der += T(nd[l]) * x[l];
+      val = x[lface];
+      const T hdn = D == 0 ? T(M.hx) : (D == 1 ? T(M.hy[nb.nidx1]) : T(M.hz));
+      der /= hdn;
+    }
+    s_nl[((f * 3 + c) * 2 + 0) * NP2 + k] = val;
+    s_nl[((f * 3 + c) * 2 + 1) * NP2 + k] = der;
+  }
+  if (need_nut && threadIdx.x < 18) {
+    const int f = threadIdx.x / 3, c = threadIdx.x % 3;
+    const FaceNb nb = face_nb(M, ex, ey, ez, f >> 1, f & 1);
+    s_nut[threadIdx.x] = nb.enr_nb >= 0 ? u[M.enr_off + nb.enr_nb * 3 + c] : T(0);
+  }
+}
+
+// Both faces of direction D: traces on both sides at the face Gauss points
+// (factorized 2-D interpolation of the node layers), numerical flux, and
+// integration against the cell's own test functions (transposed sweeps).
+template <typename T, int NP, int NQ, int NQY, bool ENR, int D>
+__device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, const T* s_nl, const T* s_nut, T* s_r,
+                                              T* s_face, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
+                                              T hy, T hz, T rt[3]) {
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr TabLayout L = tab_layout(NP, NQ, NQY);
   constexpr int T1 = D == 0 ? 1 : 0;
@@ -47,115 +131,117 @@ __device__ __forceinline__ void vel_face(const MeshDev& M, const T* __restrict__
   constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3;
   const int tid = threadIdx.x, nt = blockDim.x;
   const double* tab = M.tab;
-  const double* Sx = tab + L.S;
-  const double* Sdx = tab + L.Sd;
   const double* Sy = ENR ? tab + L.Sy : tab + L.S;
   const double* Sdy = ENR ? tab + L.Sdy : tab + L.Sd;
-  const double* St1 = T1 == 1 ? Sy : Sx;
-  const double* Sdt1 = T1 == 1 ? Sdy : Sdx;
-  const double* St2 = T2 == 1 ? Sy : Sx;
-  const double* Sdt2 = T2 == 1 ? Sdy : Sdx;
-  const double* wt1 = T1 == 1 ? (ENR ? tab + L.wy : tab + L.w) : tab + L.w;
-  const double* wt2 = T2 == 1 ? (ENR ? tab + L.wy : tab + L.w) : tab + L.w;
-  const double* ndo = tab + (S ? L.nd1 : L.nd0);   // own face at xi_D = S
-  const double* ndn = tab + (S ? L.nd0 : L.nd1);   // neighbour's face at 1 - S
+  const double* wy = ENR ? tab + L.wy : tab + L.w;
+  const double* S1 = T1 == 1 ? Sy : tab + L.S;
+  const double* Sd1 = T1 == 1 ? Sdy : tab + L.Sd;
+  const double* w1 = T1 == 1 ? wy : tab + L.w;
+  const double* S2 = T2 == 1 ? Sy : tab + L.S;
+  const double* Sd2 = T2 == 1 ? Sdy : tab + L.Sd;
+  const double* w2 = T2 == 1 ? wy : tab + L.w;
+  const double* nd0 = tab + L.nd0;
+  const double* nd1 = tab + L.nd1;
 
-  T* lay = s_big;
-  T* tr = lay + Sh::LAY;
-  T* fl = tr + Sh::TR;
+  T* lay = s_face;                 // [s][c][val|d_n][NP2]
+  T* A1 = lay + Sh::LAYO;          // [s][side][c][Sv|Sdv|Sn][q1][i2]
+  T* fl = A1 + Sh::A1;             // [s][12][pt]
+  T* B1 = fl + Sh::FL;             // [s][c][3][q1][i2]
 
-  // neighbour
-  int nidx[3] = {ex, ey, ez};
-  const int nmax[3] = {M.nx, M.ny, M.nz};
-  nidx[D] += S ? 1 : -1;
-  bool wall = false;
-  if (nidx[D] < 0 || nidx[D] >= nmax[D]) {
-    if (D == 1 && !M.fully_periodic) wall = true;
-    nidx[D] = (nidx[D] + nmax[D]) % nmax[D];
-  }
-  const int64_t enb = nidx[0] + (int64_t)M.nx * (nidx[1] + (int64_t)M.ny * nidx[2]);
-  const int64_t enr_nb = wall ? -1 : enr_index(M, nidx[0], nidx[1], nidx[2]);
   const T hown[3] = {hx, hy, hz};
-  const T hd = hown[D];
-  const T hdn = (D == 1) ? T(M.hy[nidx[1]]) : hd;
-  const T ht1 = hown[T1], ht2 = hown[T2];
-  const T tauF = wall ? T(M.pen * M.wall_mult) / hd : T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
+  const T hd = hown[D], ht1 = hown[T1], ht2 = hown[T2];
+  FaceNb nb[2];
+  T tauF[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    nb[s] = face_nb(M, ex, ey, ez, D, s);
+    const T hdn = (D == 1) ? T(M.hy[nb[s].nidx1]) : hd;
+    tauF[s] = nb[s].wall ? T(M.pen * M.wall_mult) / hd
+                         : T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
+  }
 
-  // Phase A: node layers on the face (value and normal derivative), both sides
+  // Phase A: own node layers of both faces
   for (int t = tid; t < 2 * 3 * NP2; t += nt) {
-    const int side = t / (3 * NP2), rem = t - side * 3 * NP2;
+    const int s = t / (3 * NP2), rem = t - s * 3 * NP2;
     const int c = rem / NP2, k = rem - c * NP2;
-    if (side == 1 && wall) continue;
-    const int i1 = k % NP, i2 = k / NP;
-    int pos[3];
-    pos[T1] = i1;
-    pos[T2] = i2;
-    const int lface = (side == 0 ? S : 1 - S) ? NP - 1 : 0;
-    const double* nd = side == 0 ? ndo : ndn;
-    T val = 0, der = 0;
+    int base, stride;
+    line_of<NP>(D, k % NP, k / NP, base, stride);
+    const double* nd = s ? nd1 : nd0;
+    const T* src = s_u + c * NP3 + base;
+    T der = 0;
 #pragma unroll
-    for (int l = 0; l < NP; ++l) {
-      pos[D] = l;
-      const int B = pos[0] + NP * (pos[1] + NP * pos[2]);
-      const T x = side == 0 ? s_u[c * NP3 + B] : u[(enb * 3 + c) * NP3 + B];
-      der += T(nd[l]) * x;
-      if (l == lface) val = x;
-    }
-    lay[((side * 3 + c) * 2 + 0) * NP2 + k] = val;
-    lay[((side * 3 + c) * 2 + 1) * NP2 + k] = der / (side == 0 ? hd : hdn);
+    for (int l = 0; l < NP; ++l) der += T(nd[l]) * src[l * stride];
+    lay[((s * 3 + c) * 2 + 0) * NP2 + k] = src[(s ? NP - 1 : 0) * stride];
+    lay[((s * 3 + c) * 2 + 1) * NP2 + k] = der / hd;
   }
   __syncthreads();
 
-  // Phase B: traces at the face Gauss points
-  for (int t = tid; t < 2 * 3 * FP; t += nt) {
-    const int side = t / (3 * FP), rem = t - side * 3 * FP;
-    const int c = rem / FP, pt = rem - c * FP;
-    if (side == 1 && wall) continue;
-    const int q1 = pt % Q1, q2 = pt / Q1;
-    const T* lv = lay + ((side * 3 + c) * 2 + 0) * NP2;
-    const T* ln = lay + ((side * 3 + c) * 2 + 1) * NP2;
-    T v = 0, d1 = 0, d2 = 0, dn = 0;
+  // Phase B1: sweep along t1 (node i1 -> Gauss q1) for both faces and sides
+  for (int t = tid; t < 2 * 2 * 3 * NP * Q1; t += nt) {
+    const int q1 = t % Q1;
+    int r = t / Q1;
+    const int i2 = r % NP;
+    r /= NP;
+    const int c = r % 3;
+    r /= 3;
+    const int side = r % 2, s = r / 2;
+    if (side == 1 && nb[s].wall) continue;
+    const T* lv = side == 0 ? lay + ((s * 3 + c) * 2) * NP2 : s_nl + (((2 * D + s) * 3 + c) * 2) * NP2;
+    const T* ln = lv + NP2;
+    T sv = 0, sdv = 0, sn = 0;
 #pragma unroll
-    for (int i2 = 0; i2 < NP; ++i2) {
-      T av = 0, ad = 0, an = 0;
-#pragma unroll
-      for (int i1 = 0; i1 < NP; ++i1) {
-        const T x = lv[i1 + NP * i2];
-        av += T(St1[q1 * NP + i1]) * x;
-        ad += T(Sdt1[q1 * NP + i1]) * x;
-        an += T(St1[q1 * NP + i1]) * ln[i1 + NP * i2];
-      }
-      const T s2 = T(St2[q2 * NP + i2]), sd2 = T(Sdt2[q2 * NP + i2]);
-      v += s2 * av;
-      d1 += s2 * ad;
-      d2 += sd2 * av;
-      dn += s2 * an;
+    for (int i1 = 0; i1 < NP; ++i1) {
+      const T a = T(S1[q1 * NP + i1]), ad = T(Sd1[q1 * NP + i1]);
+      sv += a * lv[i1 + NP * i2];
+      sdv += ad * lv[i1 + NP * i2];
+      sn += a * ln[i1 + NP * i2];
     }
-    T* o = tr + (side * 3 + c) * 4 * Sh::FMAX;
-    o[0 * Sh::FMAX + pt] = v;
-    o[1 * Sh::FMAX + pt] = d1 / ht1;
-    o[2 * Sh::FMAX + pt] = d2 / ht2;
-    o[3 * Sh::FMAX + pt] = dn;
+    T* o = A1 + (((s * 2 + side) * 3 + c) * 3) * (Q1 * NP) + q1 * NP + i2;
+    o[0] = sv;
+    o[Q1 * NP] = sdv;
+    o[2 * Q1 * NP] = sn;
   }
   __syncthreads();
 
-  // Phase C: numerical flux at each face point
+  // Phase C: traces at each face point (sweep along t2), then the flux
   const T nu = T(M.nu), theta = T(M.theta);
-  const T sg = S ? T(1) : T(-1);
-  for (int pt = tid; pt < FP; pt += nt) {
+  for (int t = tid; t < 2 * FP; t += nt) {
+    const int s = t / FP, pt = t - s * FP;
     const int q1 = pt % Q1, q2 = pt / Q1;
+    const T sg = s ? T(1) : T(-1);
+    T tr[2][3][4];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 1 && nb[s].wall) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T* a = A1 + (((s * 2 + side) * 3 + c) * 3) * (Q1 * NP) + q1 * NP;
+        T v = 0, d1 = 0, d2 = 0, dn = 0;
+#pragma unroll
+        for (int i2 = 0; i2 < NP; ++i2) {
+          const T b2 = T(S2[q2 * NP + i2]), bd2 = T(Sd2[q2 * NP + i2]);
+          v += b2 * a[i2];
+          d1 += b2 * a[Q1 * NP + i2];
+          d2 += bd2 * a[i2];
+          dn += b2 * a[2 * Q1 * NP + i2];
+        }
+        tr[side][c][0] = v;
+        tr[side][c][1] = d1 / ht1;
+        tr[side][c][2] = d2 / ht2;
+        tr[side][c][3] = dn;
+      }
+    }
     T um[3], up[3], gm[3][3], gp[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T* o = tr + (0 * 3 + c) * 4 * Sh::FMAX;
-      um[c] = o[pt];
-      gm[c][T1] = o[Sh::FMAX + pt];
-      gm[c][T2] = o[2 * Sh::FMAX + pt];
-      gm[c][D] = o[3 * Sh::FMAX + pt];
+      um[c] = tr[0][c][0];
+      gm[c][T1] = tr[0][c][1];
+      gm[c][T2] = tr[0][c][2];
+      gm[c][D] = tr[0][c][3];
     }
     T psim = 0, gpsim[3] = {0, 0, 0};
     if (ENR) {
-      const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + 2 * D + S] + pt) * 4;
+      const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + 2 * D + s] + pt) * 4;
       psim = T(ps[0]);
       gpsim[0] = T(ps[1]);
       gpsim[1] = T(ps[2]);
@@ -167,7 +253,7 @@ __device__ __forceinline__ void vel_face(const MeshDev& M, const T* __restrict__
         for (int k = 0; k < 3; ++k) gm[c][k] += s_ut[c] * gpsim[k];
       }
     }
-    if (wall) {
+    if (nb[s].wall) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         up[c] = -um[c];
@@ -177,19 +263,19 @@ __device__ __forceinline__ void vel_face(const MeshDev& M, const T* __restrict__
     } else {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T* o = tr + (1 * 3 + c) * 4 * Sh::FMAX;
-        up[c] = o[pt];
-        gp[c][T1] = o[Sh::FMAX + pt];
-        gp[c][T2] = o[2 * Sh::FMAX + pt];
-        gp[c][D] = o[3 * Sh::FMAX + pt];
+        up[c] = tr[1][c][0];
+        gp[c][T1] = tr[1][c][1];
+        gp[c][T2] = tr[1][c][2];
+        gp[c][D] = tr[1][c][3];
       }
-      if (enr_nb >= 0) {
-        const double* ps = M.psi + ((size_t)enr_nb * M.psi_pts + M.psi_off[1 + 2 * D + (1 - S)] + pt) * 4;
+      if (nb[s].enr_nb >= 0) {
+        const double* ps =
+            M.psi + ((size_t)nb[s].enr_nb * M.psi_pts + M.psi_off[1 + 2 * D + (1 - s)] + pt) * 4;
         const T psip = T(ps[0]);
         const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T ut = u[M.enr_off + enr_nb * 3 + c];
+          const T ut = s_nut[(2 * D + s) * 3 + c];
           up[c] += psip * ut;
 #pragma unroll
           for (int k = 0; k < 3; ++k) gp[c][k] += ut * gpp[k];
@@ -200,70 +286,91 @@ __device__ __forceinline__ void vel_face(const MeshDev& M, const T* __restrict__
     const T unm = sg * um[D], unp = sg * up[D];
     const T am = unm < 0 ? -unm : unm, ap = unp < 0 ? -unp : unp;
     const T lam = T(2) * (am > ap ? am : ap);
-    const T wf = T(wt1[q1]) * T(wt2[q2]) * ht1 * ht2;
-    T jmp[3], fv[3];
+    const T wf = T(w1[q1]) * T(w2[q2]) * ht1 * ht2;
+    const T tau = tauF[s];
+    T jmp[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) jmp[c] = um[c] - up[c];
+    T* fo = fl + s * 12 * FP + pt;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       // {{2 nu eps(u)}} n = nu/2 (grad u- + grad u-^T + grad u+ + grad u+^T) n
       const T visc = (gm[c][D] + gm[D][c] + gp[c][D] + gp[D][c]) * sg;
-      fv[c] = T(0.5) * (um[c] * unm + up[c] * unp) + T(0.5) * lam * jmp[c] - T(0.5) * nu * visc +
-              tauF * nu * jmp[c];
-      fl[c * Sh::FMAX + pt] = wf * fv[c];
+      const T fv = T(0.5) * (um[c] * unm + up[c] * unp) + T(0.5) * lam * jmp[c] - T(0.5) * nu * visc +
+                   tau * nu * jmp[c];
+      fo[c * FP] = wf * fv;
+      if (ENR) rt[c] += wf * psim * fv;
     }
-    // F_g = -theta nu sym(jmp (x) n): entries [c][k] = -theta nu/2 (jmp_c n_k + jmp_k n_c)
+    // F_g[c][k] = -theta nu/2 (jmp_c n_k + jmp_k n_c)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const T nk = (k == D) ? sg : T(0), nc = (c == D) ? sg : T(0);
         const T Fg = -theta * nu * T(0.5) * (jmp[c] * nk + jmp[k] * nc);
-        fl[(3 + 3 * c + k) * Sh::FMAX + pt] = wf * Fg;
+        fo[(3 + 3 * c + k) * FP] = wf * Fg;
         if (ENR) rt[c] += wf * Fg * gpsim[k];
       }
-    if (ENR)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rt[c] += wf * psim * fv[c];
   }
   __syncthreads();
 
-  // Phase D: integrate against the own test functions (transpose of A/B)
+  // Phase D1: transposed sweep along t2 (q2 -> i2)
+  for (int t = tid; t < 2 * 3 * Q1 * NP; t += nt) {
+    const int i2 = t % NP;
+    int r = t / NP;
+    const int q1 = r % Q1;
+    r /= Q1;
+    const int c = r % 3, s = r / 3;
+    const T* fo = fl + s * 12 * FP;
+    const T* fv = fo + c * FP;
+    const T* ft1 = fo + (3 + 3 * c + T1) * FP;
+    const T* ft2 = fo + (3 + 3 * c + T2) * FP;
+    const T* fnn = fo + (3 + 3 * c + D) * FP;
+    T a0 = 0, a1 = 0, a3 = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < Q2; ++q2) {
+      const int pt = q1 + Q1 * q2;
+      const T b2 = T(S2[q2 * NP + i2]), bd2 = T(Sd2[q2 * NP + i2]);
+      a0 += b2 * fv[pt] + bd2 * ft2[pt] / ht2;
+      a1 += b2 * ft1[pt];
+      a3 += b2 * fnn[pt];
+    }
+    T* o = B1 + ((s * 3 + c) * 3) * (Q1 * NP) + q1 * NP + i2;
+    o[0] = a0;
+    o[Q1 * NP] = a1;
+    o[2 * Q1 * NP] = a3;
+  }
+  __syncthreads();
+
+  // Phase D2: transposed sweep along t1 (q1 -> i1) and scatter onto the line
+  // of nodes along D (value test on the face layer, normal-derivative test on
+  // every layer); one thread per line, both faces, so no write conflicts.
   for (int t = tid; t < 3 * NP2; t += nt) {
     const int c = t / NP2, k = t - c * NP2;
     const int i1 = k % NP, i2 = k / NP;
-    const T* fvc = fl + c * Sh::FMAX;
-    const T* ft1 = fl + (3 + 3 * c + T1) * Sh::FMAX;
-    const T* ft2 = fl + (3 + 3 * c + T2) * Sh::FMAX;
-    const T* fnn = fl + (3 + 3 * c + D) * Sh::FMAX;
-    T rv = 0, bn = 0;
+    T rv[2], bn[2];
 #pragma unroll
-    for (int q2 = 0; q2 < Q2; ++q2) {
-      T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int s = 0; s < 2; ++s) {
+      const T* b = B1 + ((s * 3 + c) * 3) * (Q1 * NP) + i2;
+      T v = 0, n = 0;
 #pragma unroll
       for (int q1 = 0; q1 < Q1; ++q1) {
-        const int pt = q1 + Q1 * q2;
-        const T s1 = T(St1[q1 * NP + i1]), sd1 = T(Sdt1[q1 * NP + i1]);
-        a0 += s1 * fvc[pt];
-        a1 += sd1 * ft1[pt];
-        a2 += s1 * ft2[pt];
-        a3 += s1 * fnn[pt];
+        const T a = T(S1[q1 * NP + i1]), ad = T(Sd1[q1 * NP + i1]);
+        v += a * b[q1 * NP] + ad * b[Q1 * NP + q1 * NP] / ht1;
+        n += a * b[2 * Q1 * NP + q1 * NP];
       }
-      const T s2 = T(St2[q2 * NP + i2]), sd2 = T(Sdt2[q2 * NP + i2]);
-      rv += s2 * (a0 + a1 / ht1) + sd2 * a2 / ht2;
-      bn += s2 * a3;
+      rv[s] = v;
+      bn[s] = n / hd;
     }
-    int pos[3];
-    pos[T1] = i1;
-    pos[T2] = i2;
-    const int lface = S ? NP - 1 : 0;
+    int base, stride;
+    line_of<NP>(D, i1, i2, base, stride);
+    T* dst = s_r + c * NP3 + base;
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
-      pos[D] = l;
-      const int B = pos[0] + NP * (pos[1] + NP * pos[2]);
-      T add = T(ndo[l]) / hd * bn;
-      if (l == lface) add += rv;
-      s_r[c * NP3 + B] += add;
+      T add = T(nd0[l]) * bn[0] + T(nd1[l]) * bn[1];
+      if (l == 0) add += rv[0];
+      if (l == NP - 1) add += rv[1];
+      dst[l * stride] += add;
     }
   }
   __syncthreads();
@@ -279,6 +386,7 @@ __global__ __launch_bounds__(256) void vel_kernel(const MeshDev M, const T* __re
   __shared__ T s_r[3 * NP3];
   __shared__ T s_big[Sh::BIG];
   __shared__ T s_ut[3];
+  __shared__ T s_nut[18];
   __shared__ T s_red[3 * 4];
   const int tid = threadIdx.x, nt = blockDim.x;
 
@@ -387,13 +495,14 @@ __global__ __launch_bounds__(256) void vel_kernel(const MeshDev M, const T* __re
     __syncthreads();
   }
 
-  // faces
-  vel_face<T, NP, NQ, NQY, ENR, 0, 0>(M, u, s_u, s_r, s_big, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
-  vel_face<T, NP, NQ, NQY, ENR, 0, 1>(M, u, s_u, s_r, s_big, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
-  vel_face<T, NP, NQ, NQY, ENR, 1, 0>(M, u, s_u, s_r, s_big, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
-  vel_face<T, NP, NQ, NQY, ENR, 1, 1>(M, u, s_u, s_r, s_big, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
-  vel_face<T, NP, NQ, NQY, ENR, 2, 0>(M, u, s_u, s_r, s_big, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
-  vel_face<T, NP, NQ, NQY, ENR, 2, 1>(M, u, s_u, s_r, s_big, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
+  // faces: neighbour layers of all six faces (one phase), then each direction
+  T* s_nl = s_big;
+  T* s_face = s_big + Sh::NL;
+  load_neighbour_layers<T, NP>(M, u, s_nl, s_nut, tab + L.nd0, tab + L.nd1, ex, ey, ez, true);
+  __syncthreads();
+  vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
+  vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
+  vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
 
   for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
   if (ENR) {

@@ -1,19 +1,485 @@
-// Poisson solve (placeholder until the solver lands).
+// Poisson solve for the singular SIP operator (pressure step of the paper's
+// dual-splitting scheme, Sec. 4.1 eq. poisson, with the operator of Sec. 4.2).
+//
+// Outer loop: flexible preconditioned conjugate gradients in FP64 (residuals,
+// norms, dot products and the solution always FP64), with the true residual
+// b - A x recomputed (residual replacement) every few iterations and before
+// accepting convergence.  Preconditioner:
+//   mixed = 0: Chebyshev polynomial of degree m in D^{-1} A, FP64;
+//   mixed = 1: the same polynomial with FP32 operator applications, or, with
+//              max_inner > 0, that many FP32 preconditioned CG iterations on
+//              the normalised residual, accumulated in FP64 dot products.
+// The Chebyshev interval is [lmax/30, 1.1 lmax], lmax from 20 Lanczos steps
+// (Jacobi-preconditioned CG coefficients) cached in the mesh handle.
+// Every reduction is a fixed-grid two-stage FP64 sum: deterministic.
+// The null space (constants) is handled by projecting b and x to zero mean.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
 #include "dgwm_internal.h"
 
+namespace dgwm {
+
+namespace {
+
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  return s;
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kRedThreads) void k_dot(const TA* __restrict__ a, const TB* __restrict__ b, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  double v = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v += (double)a[i] * (double)b[i];
+  v = block_reduce(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_sum(const T* __restrict__ a, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  double v = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v += (double)a[i];
+  v = block_reduce(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// out = sum of the kRedBlocks partials (one block, fixed order).
+__global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads / 64];
+  double v = 0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[i];
+  v = block_reduce(v, sh);
+  if (threadIdx.x == 0) *out = v;
+}
+
+template <typename T>
+__global__ void k_sub_mean(T* __restrict__ a, int64_t n, const double* __restrict__ sum) {
+  const double mean = *sum / (double)n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = (T)((double)a[i] - mean);
+}
+
+// y = b - mean(b)
+__global__ void k_copy_sub_mean(double* __restrict__ y, const double* __restrict__ b, int64_t n,
+                                const double* __restrict__ sum) {
+  const double mean = *sum / (double)n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = b[i] - mean;
+}
+
+// r = b - Ax
+__global__ void k_resid(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ ax, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = b[i] - ax[i];
+}
+
+// x += alpha p, r -= alpha q with alpha = num/den (device scalars); partial sums of r^2.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_update_xr(T* __restrict__ x, T* __restrict__ r,
+                                                          const T* __restrict__ p, const T* __restrict__ q, int64_t n,
+                                                          const double* __restrict__ num,
+                                                          const double* __restrict__ den, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  const T alpha = (T)(*num / *den);
+  double v = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    v += (double)ri * (double)ri;
+  }
+  v = block_reduce(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// p = z + beta p, beta = (num - sub) / den
+template <typename T>
+__global__ void k_update_p(T* __restrict__ p, const T* __restrict__ z, int64_t n, const double* __restrict__ num,
+                           const double* __restrict__ sub, const double* __restrict__ den) {
+  const double nb = *num - (sub ? *sub : 0.0);
+  const T beta = (T)(nb / *den);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+// Chebyshev first step: d = c Dinv r, z = d
+template <typename T>
+__global__ void k_cheb_first(T* __restrict__ z, T* __restrict__ d, const T* __restrict__ r,
+                             const T* __restrict__ dinv, int64_t n, T c) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T v = c * dinv[i] * r[i];
+    d[i] = v;
+    z[i] = v;
+  }
+}
+
+// Chebyshev step: d = c1 d + c2 Dinv (r - Az), z += d
+template <typename T>
+__global__ void k_cheb_step(T* __restrict__ z, T* __restrict__ d, const T* __restrict__ r, const T* __restrict__ az,
+                            const T* __restrict__ dinv, int64_t n, T c1, T c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T v = c1 * d[i] + c2 * dinv[i] * (r[i] - az[i]);
+    d[i] = v;
+    z[i] += v;
+  }
+}
+
+// out32 = r / sqrt(rr)
+__global__ void k_to_f32(float* __restrict__ out, const double* __restrict__ r, int64_t n,
+                         const double* __restrict__ rr) {
+  const double s = 1.0 / sqrt(*rr);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)(r[i] * s);
+}
+
+// z = sqrt(rr) * x32
+__global__ void k_from_f32(double* __restrict__ z, const float* __restrict__ x, int64_t n,
+                           const double* __restrict__ rr) {
+  const double s = sqrt(*rr);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = s * (double)x[i];
+}
+
+template <typename T>
+__global__ void k_recip(T* __restrict__ out, const double* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (T)(1.0 / d[i]);
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ a, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+template <typename T>
+__global__ void k_copy(T* __restrict__ a, const T* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = b[i];
+}
+
+// deterministic pseudo-random start vector in [-1, 1] (integer hash of the index)
+__global__ void k_hash_fill(double* __restrict__ a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = (uint64_t)i + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    a[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+// largest eigenvalue of a symmetric tridiagonal matrix (Sturm bisection)
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int n = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < n ? std::fabs(b[i]) : 0);
+    lo = std::fmin(lo, a[i] - r);
+    hi = std::fmax(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < n; ++i) {
+      if (q == 0) q = 1e-300;
+      q = a[i] - x - b[i - 1] * b[i - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-14 * std::fabs(hi); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= n) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+struct Solver {
+  const dg_mesh* m;
+  hipStream_t s;
+  int64_t n;
+  unsigned grid;
+  double *bp, *r, *z, *zold, *p, *q, *d64, *t64, *dinv, *sc, *part;
+  float *r32, *z32, *d32, *t32, *x32, *rr32, *pp32, *qq32, *dinv32;
+  int applies64 = 0, applies32 = 0, inner_total = 0;
+
+  int red_final(double* out) {
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, s, part, out);
+    return check_hip(hipGetLastError(), "reduce");
+  }
+  template <typename TA, typename TB>
+  int dot(const TA* a, const TB* b, double* out) {
+    hipLaunchKernelGGL((k_dot<TA, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, part);
+    return red_final(out);
+  }
+  template <typename T>
+  int project(T* a, double* sum) {
+    hipLaunchKernelGGL((k_sum<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, n, part);
+    int rc = red_final(sum);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_sub_mean<T>), dim3(grid), dim3(256), 0, s, a, n, sum);
+    return check_hip(hipGetLastError(), "sub mean");
+  }
+  int A64(const double* x, double* y) {
+    ++applies64;
+    return launch_poisson(m, DG_F64, x, y, s);
+  }
+  int A32(const float* x, float* y) {
+    ++applies32;
+    return launch_poisson(m, DG_F32, x, y, s);
+  }
+  // blocking read of one device scalar (NaN if the copy fails)
+  double host(const double* dev) {
+    double h = 0;
+    if (hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return NAN;
+    if (hipStreamSynchronize(s) != hipSuccess) return NAN;
+    return h;
+  }
+  // z = Cheb_m(D^{-1} A) D^{-1} r in precision T, using temporaries d, t
+  template <typename T>
+  int cheb(T* zz, const T* rr, T* dd, T* tt, const T* di, int deg, double lmin, double lmax) {
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    hipLaunchKernelGGL((k_cheb_first<T>), dim3(grid), dim3(256), 0, s, zz, dd, rr, di, n, (T)(1.0 / theta));
+    for (int k = 1; k < deg; ++k) {
+      int rc = (sizeof(T) == 8) ? A64((const double*)zz, (double*)tt) : A32((const float*)zz, (float*)tt);
+      if (rc) return rc;
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      hipLaunchKernelGGL((k_cheb_step<T>), dim3(grid), dim3(256), 0, s, zz, dd, rr, tt, di, n,
+                         (T)(rho_new * rho), (T)(2.0 * rho_new / delta));
+      rho = rho_new;
+    }
+    return check_hip(hipGetLastError(), "chebyshev");
+  }
+};
+
+}  // namespace
+}  // namespace dgwm
+
 using namespace dgwm;
+
+namespace {
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t solve_bytes(const dg_mesh* m) {
+  const size_t n = (size_t)m->n_p;
+  return 9 * up256(n * sizeof(double)) + 9 * up256(n * sizeof(float)) + up256(64 * sizeof(double)) +
+         up256(kRedBlocks * sizeof(double));
+}
+
+}  // namespace
 
 extern "C" {
 
 int64_t dg_solve_workspace_bytes(const dg_mesh* m, const dg_solve_params* sp) {
-  (void)m;
-  (void)sp;
-  return set_error(DG_ERR_UNSUPPORTED, "solver not built");
+  if (!m || !sp) return set_error(DG_ERR_ARG, "mesh/params is NULL");
+  return (int64_t)solve_bytes(m);
 }
 
 int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* b, double* x, void* ws,
                      size_t ws_bytes, dg_solve_stats* st, void* stream) {
-  (void)m; (void)sp; (void)b; (void)x; (void)ws; (void)ws_bytes; (void)st; (void)stream;
-  return set_error(DG_ERR_UNSUPPORTED, "solver not built");
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!m || !sp || !b || !x || !ws) return set_error(DG_ERR_ARG, "mesh/params/b/x/workspace is NULL");
+  if (ws_bytes < solve_bytes(m)) return set_error(DG_ERR_WORKSPACE, "solve workspace too small");
+  if (!(sp->rtol > 0) || sp->cheb_degree < 1 || sp->max_inner < 0 || sp->max_outer < 1)
+    return set_error(DG_ERR_ARG, "invalid solve parameters");
+  if (b == x) return set_error(DG_ERR_ARG, "b and x must not alias");
+  Solver S;
+  S.m = m;
+  S.s = static_cast<hipStream_t>(stream);
+  S.n = m->n_p;
+  S.grid = (unsigned)std::min<int64_t>((S.n + 255) / 256, 2048);
+  char* w = static_cast<char*>(ws);
+  auto take64 = [&](double*& p) { p = reinterpret_cast<double*>(w); w += up256(S.n * sizeof(double)); };
+  auto take32 = [&](float*& p) { p = reinterpret_cast<float*>(w); w += up256(S.n * sizeof(float)); };
+  take64(S.bp); take64(S.r); take64(S.z); take64(S.zold); take64(S.p); take64(S.q); take64(S.d64); take64(S.t64);
+  take64(S.dinv);
+  take32(S.r32); take32(S.z32); take32(S.d32); take32(S.t32); take32(S.x32); take32(S.rr32); take32(S.pp32);
+  take32(S.qq32); take32(S.dinv32);
+  S.sc = reinterpret_cast<double*>(w);
+  w += up256(64 * sizeof(double));
+  S.part = reinterpret_cast<double*>(w);
+  double* sc = S.sc;
+  enum { RZ0 = 0, RZ1 = 1, PQ = 2, RR = 3, RZX = 4, SUM = 5, NB = 6, IRZ0 = 8, IRZ1 = 9, IPQ = 10, IRR = 11 };
+  int rc;
+#define DG_TRY(expr) \
+  if ((rc = (expr))) return rc
+  hipLaunchKernelGGL((k_recip<double>), dim3(S.grid), dim3(256), 0, S.s, S.dinv, m->diag, S.n);
+  hipLaunchKernelGGL((k_recip<float>), dim3(S.grid), dim3(256), 0, S.s, S.dinv32, m->diag, S.n);
+
+  // Chebyshev interval: Lanczos estimate of lmax(D^{-1} A), cached per mesh
+  dg_mesh* mm = const_cast<dg_mesh*>(m);
+  if (!(mm->lam_max > 0)) {
+    hipLaunchKernelGGL(k_hash_fill, dim3(S.grid), dim3(256), 0, S.s, S.r, S.n);
+    DG_TRY(S.project(S.r, sc + SUM));
+    hipLaunchKernelGGL((k_fill<double>), dim3(S.grid), dim3(256), 0, S.s, S.t64, S.n, 0.0);
+    std::vector<double> al, be;
+    double rz_old = 0;
+    for (int k = 0; k < 20; ++k) {
+      hipLaunchKernelGGL((k_cheb_first<double>), dim3(S.grid), dim3(256), 0, S.s, S.z, S.d64, S.r, S.dinv, S.n, 1.0);
+      DG_TRY(S.dot(S.r, S.z, sc + RZ0));
+      const double rz = S.host(sc + RZ0);
+      if (!(rz > 0) || !std::isfinite(rz)) break;
+      if (k == 0) {
+        hipLaunchKernelGGL((k_copy<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n);
+      } else {
+        be.push_back(rz / rz_old);
+        // p = z + (rz / rz_old) p with both scalars on the device
+        hipLaunchKernelGGL((k_update_p<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n, sc + RZ0,
+                           (const double*)nullptr, sc + RZ1);
+      }
+      DG_TRY(S.A64(S.p, S.q));
+      DG_TRY(S.dot(S.p, S.q, sc + PQ));
+      const double pq = S.host(sc + PQ);
+      if (!(pq > 0)) break;
+      al.push_back(rz / pq);
+      hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, S.t64, S.r, S.p, S.q,
+                         S.n, sc + RZ0, sc + PQ, S.part);
+      hipLaunchKernelGGL((k_copy<double>), dim3(1), dim3(1), 0, S.s, sc + RZ1, sc + RZ0, (int64_t)1);
+      rz_old = rz;
+    }
+    const int kk = (int)al.size();
+    if (kk < 1) return set_error(DG_ERR_NONFINITE, "eigenvalue estimate failed");
+    std::vector<double> diag(kk), off(kk > 1 ? kk - 1 : 0);
+    for (int j = 0; j < kk; ++j) {
+      diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+      if (j + 1 < kk) off[j] = std::sqrt(be[j]) / al[j];
+    }
+    mm->lam_max = tridiag_max_eig(diag, off);
+    S.applies64 = 0;
+  }
+  const double lmax = 1.1 * mm->lam_max, lmin = mm->lam_max / 30.0;
+  const int deg = sp->cheb_degree;
+
+  // b' = b - mean(b), ||b'||
+  hipLaunchKernelGGL((k_sum<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, b, S.n, S.part);
+  DG_TRY(S.red_final(sc + SUM));
+  hipLaunchKernelGGL(k_copy_sub_mean, dim3(S.grid), dim3(256), 0, S.s, S.bp, b, S.n, sc + SUM);
+  DG_TRY(S.dot(S.bp, S.bp, sc + NB));
+  const double nb2 = S.host(sc + NB);
+  if (!std::isfinite(nb2)) return set_error(DG_ERR_NONFINITE, "non-finite right-hand side");
+  const double nb = std::sqrt(nb2);
+  dg_solve_stats stats{};
+  if (nb == 0.0) {
+    hipLaunchKernelGGL((k_fill<double>), dim3(S.grid), dim3(256), 0, S.s, x, S.n, 0.0);
+    DG_TRY(check_hip(hipStreamSynchronize(S.s), "sync"));
+    if (st) *st = stats;
+    return DG_OK;
+  }
+  DG_TRY(S.project(x, sc + SUM));
+
+  auto true_residual = [&]() -> double {
+    if (S.A64(x, S.q)) return NAN;
+    hipLaunchKernelGGL(k_resid, dim3(S.grid), dim3(256), 0, S.s, S.r, S.bp, S.q, S.n);
+    if (S.dot(S.r, S.r, sc + RR)) return NAN;
+    return std::sqrt(S.host(sc + RR));
+  };
+  // preconditioner z = M^{-1} r
+  auto precond = [&](double* zz) -> int {
+    if (!sp->mixed) return S.cheb<double>(zz, S.r, S.d64, S.t64, S.dinv, deg, lmin, lmax);
+    // normalised FP32 copy of r (||r||^2 is in sc[RR])
+    hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR);
+    if (sp->max_inner == 0) {
+      int e = S.cheb<float>(S.x32, S.r32, S.d32, S.t32, S.dinv32, deg, lmin, lmax);
+      if (e) return e;
+    } else {
+      // inner FP32 PCG, fixed iteration count (no host synchronisation)
+      hipLaunchKernelGGL((k_fill<float>), dim3(S.grid), dim3(256), 0, S.s, S.x32, S.n, 0.0f);
+      hipLaunchKernelGGL((k_copy<float>), dim3(S.grid), dim3(256), 0, S.s, S.rr32, S.r32, S.n);
+      int e = S.cheb<float>(S.z32, S.rr32, S.d32, S.t32, S.dinv32, deg, lmin, lmax);
+      if (e) return e;
+      hipLaunchKernelGGL((k_copy<float>), dim3(S.grid), dim3(256), 0, S.s, S.pp32, S.z32, S.n);
+      if ((e = S.dot(S.rr32, S.z32, sc + IRZ0))) return e;
+      int cur = IRZ0;
+      for (int j = 0; j < sp->max_inner; ++j) {
+        if ((e = S.A32(S.pp32, S.qq32))) return e;
+        if ((e = S.dot(S.pp32, S.qq32, sc + IPQ))) return e;
+        hipLaunchKernelGGL((k_update_xr<float>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, S.x32, S.rr32, S.pp32,
+                           S.qq32, S.n, sc + cur, sc + IPQ, S.part);
+        ++S.inner_total;
+        if (j + 1 == sp->max_inner) break;
+        if ((e = S.cheb<float>(S.z32, S.rr32, S.d32, S.t32, S.dinv32, deg, lmin, lmax))) return e;
+        const int nxt = cur == IRZ0 ? IRZ1 : IRZ0;
+        if ((e = S.dot(S.rr32, S.z32, sc + nxt))) return e;
+        hipLaunchKernelGGL((k_update_p<float>), dim3(S.grid), dim3(256), 0, S.s, S.pp32, S.z32, S.n, sc + nxt,
+                           (const double*)nullptr, sc + cur);
+        cur = nxt;
+      }
+    }
+    hipLaunchKernelGGL(k_from_f32, dim3(S.grid), dim3(256), 0, S.s, zz, S.x32, S.n, sc + RR);
+    return check_hip(hipGetLastError(), "preconditioner");
+  };
+
+  double rn = true_residual();
+  if (!std::isfinite(rn)) return set_error(DG_ERR_NONFINITE, "non-finite residual");
+  int it = 0;
+  bool converged = rn <= sp->rtol * nb;
+  const int max_it = sp->max_outer;
+  const int replace_every = 50;
+  if (!converged) {
+    DG_TRY(precond(S.z));
+    hipLaunchKernelGGL((k_copy<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n);
+    DG_TRY(S.dot(S.r, S.z, sc + RZ0));
+    int cur = RZ0;
+    for (it = 1; it <= max_it; ++it) {
+      DG_TRY(S.A64(S.p, S.q));
+      DG_TRY(S.dot(S.p, S.q, sc + PQ));
+      hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, x, S.r, S.p, S.q, S.n,
+                         sc + cur, sc + PQ, S.part);
+      DG_TRY(S.red_final(sc + RR));
+      rn = std::sqrt(S.host(sc + RR));
+      if (!std::isfinite(rn)) return set_error(DG_ERR_NONFINITE, "non-finite residual");
+      if (rn <= sp->rtol * nb || it % replace_every == 0) {
+        rn = true_residual();
+        if (!std::isfinite(rn)) return set_error(DG_ERR_NONFINITE, "non-finite residual");
+        if (rn <= sp->rtol * nb) {
+          converged = true;
+          break;
+        }
+      }
+      std::swap(S.z, S.zold);
+      DG_TRY(precond(S.z));
+      const int nxt = cur == RZ0 ? RZ1 : RZ0;
+      DG_TRY(S.dot(S.r, S.z, sc + nxt));
+      DG_TRY(S.dot(S.r, S.zold, sc + RZX));
+      // flexible (Polak-Ribiere) beta = (r.z - r.z_old) / rz_old
+      hipLaunchKernelGGL((k_update_p<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n, sc + nxt, sc + RZX,
+                         sc + cur);
+      cur = nxt;
+    }
+  }
+  DG_TRY(S.project(x, sc + SUM));
+  DG_TRY(check_hip(hipStreamSynchronize(S.s), "solve synchronize"));
+  stats.outer_its = it;
+  stats.inner_its_total = S.inner_total;
+  stats.op_applies_f64 = S.applies64;
+  stats.op_applies_f32 = S.applies32;
+  stats.rel_resid = rn / nb;
+  stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (st) *st = stats;
+#undef DG_TRY
+  if (!converged) return set_error(DG_ERR_NOT_CONVERGED, "iteration cap reached");
+  return DG_OK;
 }
-}
+
+}  // extern "C"
