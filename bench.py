@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--solves", type=int, default=5, help="timed Poisson solves per precision (extras)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC byte calibration)")
     args = ap.parse_args()
@@ -190,6 +191,28 @@ def main():
                        "f32_step_dofs_per_s": dofs_step / (tv32 + tp32),
                        "velocity_f32_GBps_alg": 8.0 * n_vel / tv32 / 1e9,
                        "poisson_f32_GBps_alg": 8.0 * n_p / tp32 / 1e9})
+    if not args.no_extras:
+        # Poisson solve to 1e-10 (same mesh, k=3): mixed precision vs all-FP64
+        bsol = torch.tensor(np.random.default_rng(PRESETS["precision"].seed).uniform(-1, 1, n_p), device=dev)
+        for mixed in (True, False):
+            sp = mesh.solve_params(mixed=mixed)
+            ws = mesh.solve_workspace(sp)
+            mesh.solve_poisson(bsol, sp=sp, workspace=ws)  # warm-up (eigenvalue estimate is cached)
+            times, st = [], None
+            for _ in range(args.solves):
+                x = torch.zeros_like(bsol)
+                torch.cuda.synchronize()
+                t_s = time.perf_counter()
+                x, st = mesh.solve_poisson(bsol, x=x, sp=sp, workspace=ws)
+                times.append(time.perf_counter() - t_s)
+            times = np.sort(np.array(times))
+            key = "solve_mixed" if mixed else "solve_f64"
+            extras[key] = {"median_s": float(np.median(times)), "p50_s": float(np.percentile(times, 50)),
+                           "p99_s": float(np.percentile(times, 99)), "outer_its": st.outer_its,
+                           "f64_applies": st.op_applies_f64, "f32_applies": st.op_applies_f32,
+                           "rel_resid": st.rel_resid, "solves": args.solves,
+                           "dofs_per_s": n_p / float(np.median(times))}
+        extras["solve_speedup_mixed_vs_f64"] = extras["solve_f64"]["median_s"] / extras["solve_mixed"]["median_s"]
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)  # 256 MiB
         b = torch.empty_like(a)

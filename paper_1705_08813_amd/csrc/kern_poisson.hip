@@ -16,144 +16,92 @@ namespace {
 template <typename T, int NP, int NQ>
 struct PoiShape {
   static constexpr int NP2 = NP * NP, NP3 = NP * NP * NP, NPTS = NQ * NQ * NQ, FP = NQ * NQ;
-  static constexpr int FACE = 2 * 2 * NP2 + 2 * 2 * FP + 2 * FP;  // layers, traces, fluxes
+  static constexpr int NL = 6 * 2 * NP2;   // neighbour layers [face][val|d_n][NP2]
+  static constexpr int OL = 6 * 2 * NP2;   // own layers
+  static constexpr int FL = 6 * 2 * FP;    // fluxes [face][q-test | d_n q-test][pt]
+  static constexpr int RB = 6 * 2 * NP2;   // integrated face tests [face][value | normal][NP2]
+  static constexpr int FACE = NL + OL + FL + RB;
   static constexpr int VOL = 4 * NPTS;
   static constexpr int BIG = VOL > FACE ? VOL : FACE;
 };
 
-template <typename T, int NP, int NQ, int D, int S>
-__device__ __forceinline__ void poi_face(const MeshDev& M, const T* __restrict__ p, const T* s_p, T* s_r, T* s_big,
-                                         int ex, int ey, int ez, T hx, T hy, T hz) {
-  using Sh = PoiShape<T, NP, NQ>;
-  constexpr TabLayout L = tab_layout(NP, NQ, NQ);
-  constexpr int T1 = D == 0 ? 1 : 0;
-  constexpr int T2 = D == 2 ? 1 : 2;
-  constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3, FP = Sh::FP;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  int nidx[3] = {ex, ey, ez};
-  const int nmax[3] = {M.nx, M.ny, M.nz};
-  nidx[D] += S ? 1 : -1;
-  if (nidx[D] < 0 || nidx[D] >= nmax[D]) {
-    if (D == 1 && !M.fully_periodic) return;  // wall: homogeneous Neumann, no terms
-    nidx[D] = (nidx[D] + nmax[D]) % nmax[D];
+// node index base + l * stride of the line along direction D through (a, b)
+template <int NP>
+__device__ __forceinline__ void poi_line(int D, int a, int b, int& base, int& stride) {
+  if (D == 0) {
+    base = NP * (a + NP * b);
+    stride = 1;
+  } else if (D == 1) {
+    base = a + NP * NP * b;
+    stride = NP;
+  } else {
+    base = a + NP * b;
+    stride = NP * NP;
   }
-  const int64_t enb = nidx[0] + (int64_t)M.nx * (nidx[1] + (int64_t)M.ny * nidx[2]);
-  const double* tab = M.tab;
-  const double* Sq = tab + L.S;
-  const double* wq = tab + L.w;
-  const double* ndo = tab + (S ? L.nd1 : L.nd0);
-  const double* ndn = tab + (S ? L.nd0 : L.nd1);
-  const T hown[3] = {hx, hy, hz};
-  const T hd = hown[D];
-  const T hdn = (D == 1) ? T(M.hy[nidx[1]]) : hd;
-  const T ht1 = hown[T1], ht2 = hown[T2];
-  const T tauF = T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
-  const T sg = S ? T(1) : T(-1);
+}
 
-  T* lay = s_big;                  // [side][val|dn][NP2]
-  T* tr = lay + 2 * 2 * NP2;       // [side][val|dn][FP]
-  T* fl = tr + 2 * 2 * FP;         // [fv | fn][FP]
-
-  for (int t = tid; t < 2 * NP2; t += nt) {
-    const int side = t / NP2, k = t - side * NP2;
-    const int i1 = k % NP, i2 = k / NP;
-    int pos[3];
-    pos[T1] = i1;
-    pos[T2] = i2;
-    const int lface = (side == 0 ? S : 1 - S) ? NP - 1 : 0;
-    const double* nd = side == 0 ? ndo : ndn;
-    T val = 0, der = 0;
-#pragma unroll
-    for (int l = 0; l < NP; ++l) {
-      pos[D] = l;
-      const int B = pos[0] + NP * (pos[1] + NP * pos[2]);
-      const T x = side == 0 ? s_p[B] : p[enb * NP3 + B];
-      der += T(nd[l]) * x;
-      if (l == lface) val = x;
-    }
-    lay[(side * 2 + 0) * NP2 + k] = val;
-    lay[(side * 2 + 1) * NP2 + k] = der / (side == 0 ? hd : hdn);
+// neighbour across face (D, S): -1 for a (Neumann) wall
+__device__ __forceinline__ int64_t poi_nb(const MeshDev& M, int ex, int ey, int ez, int D, int S, int& ny1) {
+  int n[3] = {ex, ey, ez};
+  const int nmax = D == 0 ? M.nx : (D == 1 ? M.ny : M.nz);
+  int j = n[D] + (S ? 1 : -1);
+  if (j < 0 || j >= nmax) {
+    if (D == 1 && !M.fully_periodic) return -1;
+    j = (j + nmax) % nmax;
   }
-  __syncthreads();
-  for (int t = tid; t < 2 * FP; t += nt) {
-    const int side = t / FP, pt = t - side * FP;
-    const int q1 = pt % NQ, q2 = pt / NQ;
-    const T* lv = lay + (side * 2 + 0) * NP2;
-    const T* ln = lay + (side * 2 + 1) * NP2;
-    T v = 0, dn = 0;
-#pragma unroll
-    for (int i2 = 0; i2 < NP; ++i2) {
-      T av = 0, an = 0;
-#pragma unroll
-      for (int i1 = 0; i1 < NP; ++i1) {
-        av += T(Sq[q1 * NP + i1]) * lv[i1 + NP * i2];
-        an += T(Sq[q1 * NP + i1]) * ln[i1 + NP * i2];
-      }
-      v += T(Sq[q2 * NP + i2]) * av;
-      dn += T(Sq[q2 * NP + i2]) * an;
-    }
-    tr[(side * 2 + 0) * FP + pt] = v;
-    tr[(side * 2 + 1) * FP + pt] = dn;
-  }
-  __syncthreads();
-  for (int pt = tid; pt < FP; pt += nt) {
-    const int q1 = pt % NQ, q2 = pt / NQ;
-    const T wf = T(wq[q1]) * T(wq[q2]) * ht1 * ht2;
-    const T jmp = tr[0 * FP + pt] - tr[2 * FP + pt];
-    const T avg_n = T(0.5) * (tr[1 * FP + pt] + tr[3 * FP + pt]) * sg;
-    fl[pt] = wf * (-avg_n + tauF * jmp);     // tested with q
-    fl[FP + pt] = wf * (T(-0.5) * jmp * sg); // tested with d q / d x_D
-  }
-  __syncthreads();
-  for (int k = tid; k < NP2; k += nt) {
-    const int i1 = k % NP, i2 = k / NP;
-    T rv = 0, bn = 0;
-#pragma unroll
-    for (int q2 = 0; q2 < NQ; ++q2) {
-      T a0 = 0, a1 = 0;
-#pragma unroll
-      for (int q1 = 0; q1 < NQ; ++q1) {
-        const T s1 = T(Sq[q1 * NP + i1]);
-        a0 += s1 * fl[q1 + NQ * q2];
-        a1 += s1 * fl[FP + q1 + NQ * q2];
-      }
-      rv += T(Sq[q2 * NP + i2]) * a0;
-      bn += T(Sq[q2 * NP + i2]) * a1;
-    }
-    int pos[3];
-    pos[T1] = i1;
-    pos[T2] = i2;
-    const int lface = S ? NP - 1 : 0;
-#pragma unroll
-    for (int l = 0; l < NP; ++l) {
-      pos[D] = l;
-      const int B = pos[0] + NP * (pos[1] + NP * pos[2]);
-      T add = T(ndo[l]) / hd * bn;
-      if (l == lface) add += rv;
-      s_r[B] += add;
-    }
-  }
-  __syncthreads();
+  n[D] = j;
+  ny1 = n[1];
+  return n[0] + (int64_t)M.nx * (n[1] + (int64_t)M.ny * n[2]);
 }
 
 template <typename T, int NP, int NQ>
 __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y) {
   using Sh = PoiShape<T, NP, NQ>;
   constexpr TabLayout L = tab_layout(NP, NQ, NQ);
-  constexpr int NP3 = Sh::NP3, NPTS = Sh::NPTS;
+  constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3, NPTS = Sh::NPTS, FP = Sh::FP;
   __shared__ T s_p[NP3];
   __shared__ T s_r[NP3];
+  __shared__ T s_nl[Sh::NL];
   __shared__ T s_big[Sh::BIG];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t e = blockIdx.x;
   const int ex = (int)(e % M.nx), ey = (int)((e / M.nx) % M.ny), ez = (int)(e / ((int64_t)M.nx * M.ny));
   const T hx = T(M.hx), hz = T(M.hz), hy = T(M.hy[ey]);
+  auto hdir = [&](int d) { return d == 0 ? hx : (d == 1 ? hy : hz); };
   const double* Sq = M.tab + L.S;
   const double* Dq = M.tab + L.D;
   const double* wq = M.tab + L.w;
+  const double* nd0 = M.tab + L.nd0;
+  const double* nd1 = M.tab + L.nd1;
 
+  // own values and the six neighbour face layers (value, normal derivative)
   for (int i = tid; i < NP3; i += nt) s_p[i] = p[e * NP3 + i];
+  for (int t = tid; t < 6 * NP2; t += nt) {
+    const int f = t / NP2, k = t - f * NP2;
+    const int D = f >> 1, S = f & 1;
+    int ny1 = 0;
+    const int64_t nb = poi_nb(M, ex, ey, ez, D, S, ny1);
+    T val = 0, der = 0;
+    if (nb >= 0) {
+      int base, stride;
+      poi_line<NP>(D, k % NP, k / NP, base, stride);
+      const T* src = p + nb * NP3 + base;
+      const double* nd = S ? nd0 : nd1;  // neighbour's face is at xi_D = 1 - S
+      T x[NP];
+#pragma unroll
+      for (int l = 0; l < NP; ++l) x[l] = src[l * stride];
+#pragma unroll
+      for (int l = 0; l < NP; ++l) der += T(nd[l]) * x[l];
+      val = x[S ? 0 : NP - 1];
+      const T hdn = D == 1 ? T(M.hy[ny1]) : hdir(D);
+      der /= hdn;
+    }
+    s_nl[(f * 2 + 0) * NP2 + k] = val;
+    s_nl[(f * 2 + 1) * NP2 + k] = der;
+  }
   __syncthreads();
+
+  // volume term: (grad q, grad p) by sum factorization
   T* s_val = s_big;
   T* s_grad = s_big + NPTS;  // [d][pt]
   {
@@ -194,13 +142,105 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
     sweep<0, NQ, NP, NP, NP, true, false>(tA, 0, s_r, 0, Sq, T(1), 1);
     __syncthreads();
   }
-  poi_face<T, NP, NQ, 0, 0>(M, p, s_p, s_r, s_big, ex, ey, ez, hx, hy, hz);
-  poi_face<T, NP, NQ, 0, 1>(M, p, s_p, s_r, s_big, ex, ey, ez, hx, hy, hz);
-  poi_face<T, NP, NQ, 1, 0>(M, p, s_p, s_r, s_big, ex, ey, ez, hx, hy, hz);
-  poi_face<T, NP, NQ, 1, 1>(M, p, s_p, s_r, s_big, ex, ey, ez, hx, hy, hz);
-  poi_face<T, NP, NQ, 2, 0>(M, p, s_p, s_r, s_big, ex, ey, ez, hx, hy, hz);
-  poi_face<T, NP, NQ, 2, 1>(M, p, s_p, s_r, s_big, ex, ey, ez, hx, hy, hz);
-  for (int i = tid; i < NP3; i += nt) y[e * NP3 + i] = s_r[i];
+
+  // face terms of all six faces
+  T* ol = s_big;              // own layers [face][val|d_n][NP2]
+  T* fl = ol + Sh::OL;        // fluxes [face][2][FP]
+  T* rb = fl + Sh::FL;        // [face][value test | normal test][NP2]
+  for (int t = tid; t < 6 * NP2; t += nt) {
+    const int f = t / NP2, k = t - f * NP2;
+    const int D = f >> 1, S = f & 1;
+    int base, stride;
+    poi_line<NP>(D, k % NP, k / NP, base, stride);
+    const double* nd = S ? nd1 : nd0;
+    T der = 0;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) der += T(nd[l]) * s_p[base + l * stride];
+    ol[(f * 2 + 0) * NP2 + k] = s_p[base + (S ? NP - 1 : 0) * stride];
+    ol[(f * 2 + 1) * NP2 + k] = der / hdir(D);
+  }
+  __syncthreads();
+  // traces of both sides at the face Gauss points, then the SIP flux
+  for (int t = tid; t < 6 * FP; t += nt) {
+    const int f = t / FP, pt = t - f * FP;
+    const int D = f >> 1, S = f & 1;
+    int ny1 = 0;
+    if (poi_nb(M, ex, ey, ez, D, S, ny1) < 0) {
+      fl[(f * 2 + 0) * FP + pt] = 0;
+      fl[(f * 2 + 1) * FP + pt] = 0;
+      continue;
+    }
+    const int q1 = pt % NQ, q2 = pt / NQ;
+    const T* lo = ol + f * 2 * NP2;
+    const T* ln = s_nl + f * 2 * NP2;
+    T vm = 0, dm = 0, vp = 0, dp = 0;
+#pragma unroll
+    for (int i2 = 0; i2 < NP; ++i2) {
+      T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) {
+        const T s1 = T(Sq[q1 * NP + i1]);
+        a0 += s1 * lo[i1 + NP * i2];
+        a1 += s1 * lo[NP2 + i1 + NP * i2];
+        a2 += s1 * ln[i1 + NP * i2];
+        a3 += s1 * ln[NP2 + i1 + NP * i2];
+      }
+      const T s2 = T(Sq[q2 * NP + i2]);
+      vm += s2 * a0;
+      dm += s2 * a1;
+      vp += s2 * a2;
+      dp += s2 * a3;
+    }
+    const int T1 = D == 0 ? 1 : 0, T2 = D == 2 ? 1 : 2;
+    const T ht1 = hdir(T1), ht2 = hdir(T2), hd = hdir(D);
+    const T hdn = D == 1 ? T(M.hy[ny1]) : hd;
+    const T tauF = T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
+    const T sg = S ? T(1) : T(-1);
+    const T wf = T(wq[q1]) * T(wq[q2]) * ht1 * ht2;
+    const T jmp = vm - vp;
+    const T avg_n = T(0.5) * (dm + dp) * sg;
+    fl[(f * 2 + 0) * FP + pt] = wf * (-avg_n + tauF * jmp);      // tested with q
+    fl[(f * 2 + 1) * FP + pt] = wf * (T(-0.5) * jmp * sg);       // tested with d q / d x_D
+  }
+  __syncthreads();
+  // integrate against the face traces of the test functions
+  for (int t = tid; t < 6 * NP2; t += nt) {
+    const int f = t / NP2, k = t - f * NP2;
+    const int i1 = k % NP, i2 = k / NP;
+    const T* a = fl + f * 2 * FP;
+    T rv = 0, bn = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < NQ; ++q2) {
+      T a0 = 0, a1 = 0;
+#pragma unroll
+      for (int q1 = 0; q1 < NQ; ++q1) {
+        const T s1 = T(Sq[q1 * NP + i1]);
+        a0 += s1 * a[q1 + NQ * q2];
+        a1 += s1 * a[FP + q1 + NQ * q2];
+      }
+      rv += T(Sq[q2 * NP + i2]) * a0;
+      bn += T(Sq[q2 * NP + i2]) * a1;
+    }
+    rb[(f * 2 + 0) * NP2 + k] = rv;
+    rb[(f * 2 + 1) * NP2 + k] = bn / hdir(f >> 1);
+  }
+  __syncthreads();
+  // scatter: every node gathers the contributions of the six faces
+  for (int B = tid; B < NP3; B += nt) {
+    const int ii[3] = {B % NP, (B / NP) % NP, B / NP2};
+    T acc = s_r[B];
+#pragma unroll
+    for (int D = 0; D < 3; ++D) {
+      const int a = D == 0 ? ii[1] : ii[0];
+      const int b = D == 2 ? ii[1] : ii[2];
+      const int k = a + NP * b;
+      const int l = ii[D];
+      acc += T(nd0[l]) * rb[((2 * D + 0) * 2 + 1) * NP2 + k] + T(nd1[l]) * rb[((2 * D + 1) * 2 + 1) * NP2 + k];
+      if (l == 0) acc += rb[((2 * D + 0) * 2 + 0) * NP2 + k];
+      if (l == NP - 1) acc += rb[((2 * D + 1) * 2 + 0) * NP2 + k];
+    }
+    y[e * NP3 + B] = acc;
+  }
 }
 
 // Diagonal of A for box cells.  The basis is a tensor product, so every term
