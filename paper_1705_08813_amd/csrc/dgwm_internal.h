@@ -6,7 +6,7 @@
 #include <cstdint>
 #include <string>
 
-#include "../../include/dgwm.h"
+#include "dgwm.h"
 
 namespace dgwm {
 

@@ -42,10 +42,11 @@ __device__ __forceinline__ int64_t enr_index(const MeshDev& M, int ex, int ey, i
 //   mat: row-major, out = mat * in (mat is MO x NI) or, with TR, out = mat^T in
 //        (mat is NI x MO).  ADD accumulates into out.  Every output is scaled.
 // One thread per pencil (line along DIR) and component; the pencil is kept in
-// registers, the matrix entries are uniform across the wavefront.
-template <int DIR, int I0, int I1, int I2, int MO, bool TR, bool ADD, typename T>
+// registers, the matrix entries are uniform across the wavefront (read from
+// LDS as broadcasts when `mat` points there).
+template <int DIR, int I0, int I1, int I2, int MO, bool TR, bool ADD, typename T, typename MT>
 __device__ __forceinline__ void sweep(const T* __restrict__ in, int IS, T* __restrict__ out, int OS,
-                                      const double* __restrict__ mat, T scale, int ncomp) {
+                                      const MT* __restrict__ mat, T scale, int ncomp) {
   constexpr int NI = DIR == 0 ? I0 : (DIR == 1 ? I1 : I2);
   constexpr int O0 = DIR == 0 ? MO : I0;
   constexpr int O1 = DIR == 1 ? MO : I1;

@@ -63,19 +63,24 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
   __shared__ T s_r[NP3];
   __shared__ T s_nl[Sh::NL];
   __shared__ T s_big[Sh::BIG];
+  __shared__ T s_ft[NQ * NP + NQ + 2 * NP];  // S, w, N'(0), N'(1) for the face phases
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t e = blockIdx.x;
   const int ex = (int)(e % M.nx), ey = (int)((e / M.nx) % M.ny), ez = (int)(e / ((int64_t)M.nx * M.ny));
   const T hx = T(M.hx), hz = T(M.hz), hy = T(M.hy[ey]);
   auto hdir = [&](int d) { return d == 0 ? hx : (d == 1 ? hy : hz); };
-  const double* Sq = M.tab + L.S;
+  const double* Sq = M.tab + L.S;  // volume sweeps: uniform indices, scalar cache
   const double* Dq = M.tab + L.D;
   const double* wq = M.tab + L.w;
   const double* nd0 = M.tab + L.nd0;
   const double* nd1 = M.tab + L.nd1;
 
-  // own values and the six neighbour face layers (value, normal derivative)
+  // own values, face tables, and the six neighbour face layers (value, normal derivative)
   for (int i = tid; i < NP3; i += nt) s_p[i] = p[e * NP3 + i];
+  for (int i = tid; i < NQ * NP + NQ + 2 * NP; i += nt) {
+    const int o = i < NQ * NP ? L.S + i : (i < NQ * NP + NQ ? L.w + i - NQ * NP : L.nd0 + i - NQ * NP - NQ);
+    s_ft[i] = T(M.tab[o]);
+  }
   for (int t = tid; t < 6 * NP2; t += nt) {
     const int f = t / NP2, k = t - f * NP2;
     const int D = f >> 1, S = f & 1;
@@ -143,7 +148,11 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
     __syncthreads();
   }
 
-  // face terms of all six faces
+  // face terms of all six faces (tables from LDS: their indices vary across lanes)
+  const T* fS = s_ft;
+  const T* fw = s_ft + NQ * NP;
+  const T* fnd0 = fw + NQ;
+  const T* fnd1 = fnd0 + NP;
   T* ol = s_big;              // own layers [face][val|d_n][NP2]
   T* fl = ol + Sh::OL;        // fluxes [face][2][FP]
   T* rb = fl + Sh::FL;        // [face][value test | normal test][NP2]
@@ -152,7 +161,7 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
     const int D = f >> 1, S = f & 1;
     int base, stride;
     poi_line<NP>(D, k % NP, k / NP, base, stride);
-    const double* nd = S ? nd1 : nd0;
+    const T* nd = S ? fnd1 : fnd0;
     T der = 0;
 #pragma unroll
     for (int l = 0; l < NP; ++l) der += T(nd[l]) * s_p[base + l * stride];
@@ -179,13 +188,13 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
       T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
       for (int i1 = 0; i1 < NP; ++i1) {
-        const T s1 = T(Sq[q1 * NP + i1]);
+        const T s1 = (fS[q1 * NP + i1]);
         a0 += s1 * lo[i1 + NP * i2];
         a1 += s1 * lo[NP2 + i1 + NP * i2];
         a2 += s1 * ln[i1 + NP * i2];
         a3 += s1 * ln[NP2 + i1 + NP * i2];
       }
-      const T s2 = T(Sq[q2 * NP + i2]);
+      const T s2 = (fS[q2 * NP + i2]);
       vm += s2 * a0;
       dm += s2 * a1;
       vp += s2 * a2;
@@ -196,7 +205,7 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
     const T hdn = D == 1 ? T(M.hy[ny1]) : hd;
     const T tauF = T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
     const T sg = S ? T(1) : T(-1);
-    const T wf = T(wq[q1]) * T(wq[q2]) * ht1 * ht2;
+    const T wf = (fw[q1]) * (fw[q2]) * ht1 * ht2;
     const T jmp = vm - vp;
     const T avg_n = T(0.5) * (dm + dp) * sg;
     fl[(f * 2 + 0) * FP + pt] = wf * (-avg_n + tauF * jmp);      // tested with q
@@ -214,12 +223,12 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
       T a0 = 0, a1 = 0;
 #pragma unroll
       for (int q1 = 0; q1 < NQ; ++q1) {
-        const T s1 = T(Sq[q1 * NP + i1]);
+        const T s1 = (fS[q1 * NP + i1]);
         a0 += s1 * a[q1 + NQ * q2];
         a1 += s1 * a[FP + q1 + NQ * q2];
       }
-      rv += T(Sq[q2 * NP + i2]) * a0;
-      bn += T(Sq[q2 * NP + i2]) * a1;
+      rv += (fS[q2 * NP + i2]) * a0;
+      bn += (fS[q2 * NP + i2]) * a1;
     }
     rb[(f * 2 + 0) * NP2 + k] = rv;
     rb[(f * 2 + 1) * NP2 + k] = bn / hdir(f >> 1);
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* _
       const int b = D == 2 ? ii[1] : ii[2];
       const int k = a + NP * b;
       const int l = ii[D];
-      acc += T(nd0[l]) * rb[((2 * D + 0) * 2 + 1) * NP2 + k] + T(nd1[l]) * rb[((2 * D + 1) * 2 + 1) * NP2 + k];
+      acc += (fnd0[l]) * rb[((2 * D + 0) * 2 + 1) * NP2 + k] + (fnd1[l]) * rb[((2 * D + 1) * 2 + 1) * NP2 + k];
       if (l == 0) acc += rb[((2 * D + 0) * 2 + 0) * NP2 + k];
       if (l == NP - 1) acc += rb[((2 * D + 1) * 2 + 0) * NP2 + k];
     }

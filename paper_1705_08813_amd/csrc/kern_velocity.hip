@@ -26,8 +26,8 @@ struct VelShape {
   static constexpr int Q1MAX = NQY > NQ ? NQY : NQ;
   static constexpr int NL = 6 * 3 * 2 * NP2;            // neighbour layers [face][c][val|d_n][NP2]
   static constexpr int LAYO = 2 * 3 * 2 * NP2;          // own layers of the two faces of one direction
-  static constexpr int A1 = 2 * 2 * 3 * 3 * Q1MAX * NP; // t1-swept traces [s][side][c][field][q1][i2]
-  static constexpr int FL = 2 * 12 * FMAX;              // fluxes [s][fv c | Fg c k][pt]
+  static constexpr int A1 = 2 * 2 * 7 * Q1MAX * NP;     // t1-swept traces [s][side][field][q1][i2]
+  static constexpr int FL = 2 * 8 * FMAX;               // fluxes [s][field][pt]
   static constexpr int B1 = 2 * 3 * 3 * Q1MAX * NP;     // t2-transposed tests [s][c][3][q1][i2]
   static constexpr int FACE = NL + LAYO + A1 + FL + B1;
   static constexpr int VOL = 12 * NPTS;
@@ -59,7 +59,6 @@ struct FaceNb {
 };
 
 __device__ __forceinline__ FaceNb face_nb(const MeshDev& M, int ex, int ey, int ez, int D, int S) {
-  int n[3] = {ex, ey, ez};
   const int nmax = D == 0 ? M.nx : (D == 1 ? M.ny : M.nz);
   int j = (D == 0 ? ex : (D == 1 ? ey : ez)) + (S ? 1 : -1);
   FaceNb f;
@@ -68,10 +67,10 @@ __device__ __forceinline__ FaceNb face_nb(const MeshDev& M, int ex, int ey, int 
     if (D == 1 && !M.fully_periodic) f.wall = true;
     j = (j + nmax) % nmax;
   }
-  n[D] = j;
-  f.enb = n[0] + (int64_t)M.nx * (n[1] + (int64_t)M.ny * n[2]);
-  f.enr_nb = f.wall ? -1 : enr_index(M, n[0], n[1], n[2]);
-  f.nidx1 = n[1];
+  const int n0 = D == 0 ? j : ex, n1 = D == 1 ? j : ey, n2 = D == 2 ? j : ez;
+  f.enb = n0 + (int64_t)M.nx * (n1 + (int64_t)M.ny * n2);
+  f.enr_nb = f.wall ? -1 : enr_index(M, n0, n1, n2);
+  f.nidx1 = n1;
   return f;
 }
 
@@ -114,13 +113,45 @@ __device__ __forceinline__ void load_neighbour_layers(const MeshDev& M, const T*
   }
 }
 
+// 1-D tables used by the face phases, staged in LDS in the working precision
+// (their indices vary across lanes there): S, S' of the wall-parallel rule and
+// of the cell's wall-normal rule, both weight vectors, N'(0) and N'(1).
+template <int NP, int NQ, int NQY>
+struct FaceTab {
+  static constexpr int Sq = 0, Sdq = Sq + NQ * NP, Sy = Sdq + NQ * NP, Sdy = Sy + NQY * NP;
+  static constexpr int wq = Sdy + NQY * NP, wy = wq + NQ, nd0 = wy + NQY, nd1 = nd0 + NP, size = nd1 + NP;
+};
+
+template <typename T, int NP, int NQ, int NQY, bool ENR>
+__device__ __forceinline__ void load_face_tab(const double* tab, T* s_tab) {
+  using TL = FaceTab<NP, NQ, NQY>;
+  constexpr TabLayout L = tab_layout(NP, NQ, NQY);
+  for (int i = threadIdx.x; i < TL::size; i += blockDim.x) {
+    double v;
+    if (i < TL::Sdq) v = tab[L.S + i];
+    else if (i < TL::Sy) v = tab[L.Sd + i - TL::Sdq];
+    else if (i < TL::Sdy) v = tab[(ENR ? L.Sy : L.S) + i - TL::Sy];
+    else if (i < TL::wq) v = tab[(ENR ? L.Sdy : L.Sd) + i - TL::Sdy];
+    else if (i < TL::wy) v = tab[L.w + i - TL::wq];
+    else if (i < TL::nd0) v = tab[(ENR ? L.wy : L.w) + i - TL::wy];
+    else if (i < TL::nd1) v = tab[L.nd0 + i - TL::nd0];
+    else v = tab[L.nd1 + i - TL::nd1];
+    s_tab[i] = T(v);
+  }
+}
+
 // Both faces of direction D: traces on both sides at the face Gauss points
 // (factorized 2-D interpolation of the node layers), numerical flux, and
 // integration against the cell's own test functions (transposed sweeps).
+//
+// With the normal n = +-e_D, the fluxes use only 8 trace fields per side:
+// u_c, d_D u_c (c = 0..2), and the tangential derivatives d_T1 u_D, d_T2 u_D
+// ({{2 nu eps(u)}} n needs (grad u + grad u^T) e_D), and the adjoint term
+// -theta nu sym(j (x) n) tests only d_D phi_c and d_T phi_D.
 template <typename T, int NP, int NQ, int NQY, bool ENR, int D>
 __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, const T* s_nl, const T* s_nut, T* s_r,
-                                              T* s_face, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
-                                              T hy, T hz, T rt[3]) {
+                                              T* s_face, const T* s_ut, const T* s_tab, int ex, int ey, int ez,
+                                              int64_t enr, T hx, T hy, T hz, T rt[3]) {
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr TabLayout L = tab_layout(NP, NQ, NQY);
   constexpr int T1 = D == 0 ? 1 : 0;
@@ -129,36 +160,35 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   constexpr int Q2 = T2 == 1 ? NQY : NQ;
   constexpr int FP = Q1 * Q2;
   constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3;
+  constexpr int QN = Q1 * NP;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const double* tab = M.tab;
-  const double* Sy = ENR ? tab + L.Sy : tab + L.S;
-  const double* Sdy = ENR ? tab + L.Sdy : tab + L.Sd;
-  const double* wy = ENR ? tab + L.wy : tab + L.w;
-  const double* S1 = T1 == 1 ? Sy : tab + L.S;
-  const double* Sd1 = T1 == 1 ? Sdy : tab + L.Sd;
-  const double* w1 = T1 == 1 ? wy : tab + L.w;
-  const double* S2 = T2 == 1 ? Sy : tab + L.S;
-  const double* Sd2 = T2 == 1 ? Sdy : tab + L.Sd;
-  const double* w2 = T2 == 1 ? wy : tab + L.w;
-  const double* nd0 = tab + L.nd0;
-  const double* nd1 = tab + L.nd1;
+  using TL = FaceTab<NP, NQ, NQY>;
+  const T* S1 = s_tab + (T1 == 1 ? TL::Sy : TL::Sq);
+  const T* Sd1 = s_tab + (T1 == 1 ? TL::Sdy : TL::Sdq);
+  const T* w1 = s_tab + (T1 == 1 ? TL::wy : TL::wq);
+  const T* S2 = s_tab + (T2 == 1 ? TL::Sy : TL::Sq);
+  const T* Sd2 = s_tab + (T2 == 1 ? TL::Sdy : TL::Sdq);
+  const T* w2 = s_tab + (T2 == 1 ? TL::wy : TL::wq);
+  const T* nd0 = s_tab + TL::nd0;
+  const T* nd1 = s_tab + TL::nd1;
+  (void)L;
 
   T* lay = s_face;                 // [s][c][val|d_n][NP2]
-  T* A1 = lay + Sh::LAYO;          // [s][side][c][Sv|Sdv|Sn][q1][i2]
-  T* fl = A1 + Sh::A1;             // [s][12][pt]
-  T* B1 = fl + Sh::FL;             // [s][c][3][q1][i2]
+  T* A1 = lay + Sh::LAYO;          // [s][side][field 0..6][q1][i2]
+  T* fl = A1 + Sh::A1;             // [s][field 0..7][pt]
+  T* B1 = fl + Sh::FL;             // [s][c][value|t1|normal][q1][i2]
 
   const T hown[3] = {hx, hy, hz};
   const T hd = hown[D], ht1 = hown[T1], ht2 = hown[T2];
-  FaceNb nb[2];
-  T tauF[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    nb[s] = face_nb(M, ex, ey, ez, D, s);
-    const T hdn = (D == 1) ? T(M.hy[nb[s].nidx1]) : hd;
-    tauF[s] = nb[s].wall ? T(M.pen * M.wall_mult) / hd
-                         : T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
-  }
+  // neighbours of the two faces (scalars, selected by s without local arrays)
+  const FaceNb nb0 = face_nb(M, ex, ey, ez, D, 0), nb1 = face_nb(M, ex, ey, ez, D, 1);
+  auto tau_of = [&](const FaceNb& nb) {
+    const T hdn = (D == 1) ? T(M.hy[nb.nidx1]) : hd;
+    return nb.wall ? T(M.pen * M.wall_mult) / hd : T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
+  };
+  const T tau0 = tau_of(nb0), tau1 = tau_of(nb1);
+  const bool wall0 = nb0.wall, wall1 = nb1.wall;
+  const int64_t enrn0 = nb0.enr_nb, enrn1 = nb1.enr_nb;
 
   // Phase A: own node layers of both faces
   for (int t = tid; t < 2 * 3 * NP2; t += nt) {
@@ -166,7 +196,7 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     const int c = rem / NP2, k = rem - c * NP2;
     int base, stride;
     line_of<NP>(D, k % NP, k / NP, base, stride);
-    const double* nd = s ? nd1 : nd0;
+    const T* nd = s ? nd1 : nd0;
     const T* src = s_u + c * NP3 + base;
     T der = 0;
 #pragma unroll
@@ -176,30 +206,26 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   }
   __syncthreads();
 
-  // Phase B1: sweep along t1 (node i1 -> Gauss q1) for both faces and sides
-  for (int t = tid; t < 2 * 2 * 3 * NP * Q1; t += nt) {
+  // Phase B1: sweep along t1 (node i1 -> Gauss q1).  Fields: 0-2 value of
+  // u_c, 3-5 normal derivative of u_c, 6 t1-derivative of u_D.
+  for (int t = tid; t < 2 * 2 * 7 * QN; t += nt) {
     const int q1 = t % Q1;
     int r = t / Q1;
     const int i2 = r % NP;
     r /= NP;
-    const int c = r % 3;
-    r /= 3;
+    const int f = r % 7;
+    r /= 7;
     const int side = r % 2, s = r / 2;
-    if (side == 1 && nb[s].wall) continue;
-    const T* lv = side == 0 ? lay + ((s * 3 + c) * 2) * NP2 : s_nl + (((2 * D + s) * 3 + c) * 2) * NP2;
-    const T* ln = lv + NP2;
-    T sv = 0, sdv = 0, sn = 0;
+    if (side == 1 && (s ? wall1 : wall0)) continue;
+    const int c = f < 3 ? f : (f < 6 ? f - 3 : D);
+    const int fld = (f >= 3 && f < 6) ? 1 : 0;
+    const T* lv = (side == 0 ? lay + ((s * 3 + c) * 2) * NP2 : s_nl + (((2 * D + s) * 3 + c) * 2) * NP2) +
+                  fld * NP2 + NP * i2;
+    const T* mat = (f == 6 ? Sd1 : S1) + q1 * NP;
+    T acc = 0;
 #pragma unroll
-    for (int i1 = 0; i1 < NP; ++i1) {
-      const T a = T(S1[q1 * NP + i1]), ad = T(Sd1[q1 * NP + i1]);
-      sv += a * lv[i1 + NP * i2];
-      sdv += ad * lv[i1 + NP * i2];
-      sn += a * ln[i1 + NP * i2];
-    }
-    T* o = A1 + (((s * 2 + side) * 3 + c) * 3) * (Q1 * NP) + q1 * NP + i2;
-    o[0] = sv;
-    o[Q1 * NP] = sdv;
-    o[2 * Q1 * NP] = sn;
+    for (int i1 = 0; i1 < NP; ++i1) acc += T(mat[i1]) * lv[i1];
+    A1[(((s * 2 + side) * 7 + f) * Q1 + q1) * NP + i2] = acc;
   }
   __syncthreads();
 
@@ -209,35 +235,26 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     const int s = t / FP, pt = t - s * FP;
     const int q1 = pt % Q1, q2 = pt / Q1;
     const T sg = s ? T(1) : T(-1);
-    T tr[2][3][4];
+    const bool wall = s ? wall1 : wall0;
+    const int64_t enr_nb = s ? enrn1 : enrn0;
+    // tr[side][0..2] u_c, [3..5] d_D u_c, [6] d_T1 u_D, [7] d_T2 u_D
+    T tr[2][8];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      if (side == 1 && nb[s].wall) continue;
+      if (side == 1 && wall) continue;
+      const T* a = A1 + ((s * 2 + side) * 7) * QN + q1 * NP;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T* a = A1 + (((s * 2 + side) * 3 + c) * 3) * (Q1 * NP) + q1 * NP;
-        T v = 0, d1 = 0, d2 = 0, dn = 0;
+      for (int f = 0; f < 7; ++f) {
+        T v = 0;
 #pragma unroll
-        for (int i2 = 0; i2 < NP; ++i2) {
-          const T b2 = T(S2[q2 * NP + i2]), bd2 = T(Sd2[q2 * NP + i2]);
-          v += b2 * a[i2];
-          d1 += b2 * a[Q1 * NP + i2];
-          d2 += bd2 * a[i2];
-          dn += b2 * a[2 * Q1 * NP + i2];
-        }
-        tr[side][c][0] = v;
-        tr[side][c][1] = d1 / ht1;
-        tr[side][c][2] = d2 / ht2;
-        tr[side][c][3] = dn;
+        for (int i2 = 0; i2 < NP; ++i2) v += T(S2[q2 * NP + i2]) * a[f * QN + i2];
+        tr[side][f] = v;
       }
-    }
-    T um[3], up[3], gm[3][3], gp[3][3];
+      T d2 = 0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      um[c] = tr[0][c][0];
-      gm[c][T1] = tr[0][c][1];
-      gm[c][T2] = tr[0][c][2];
-      gm[c][D] = tr[0][c][3];
+      for (int i2 = 0; i2 < NP; ++i2) d2 += T(Sd2[q2 * NP + i2]) * a[D * QN + i2];
+      tr[side][6] /= ht1;
+      tr[side][7] = d2 / ht2;
     }
     T psim = 0, gpsim[3] = {0, 0, 0};
     if (ENR) {
@@ -248,97 +265,91 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
       gpsim[2] = T(ps[3]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        um[c] += psim * s_ut[c];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gm[c][k] += s_ut[c] * gpsim[k];
+        tr[0][c] += psim * s_ut[c];
+        tr[0][3 + c] += s_ut[c] * gpsim[D];
       }
+      tr[0][6] += s_ut[D] * gpsim[T1];
+      tr[0][7] += s_ut[D] * gpsim[T2];
     }
-    if (nb[s].wall) {
+    if (wall) {
+#pragma unroll
+      for (int f = 0; f < 8; ++f) tr[1][f] = (f < 3) ? -tr[0][f] : tr[0][f];
+    } else if (enr_nb >= 0) {
+      const double* ps = M.psi + ((size_t)enr_nb * M.psi_pts + M.psi_off[1 + 2 * D + (1 - s)] + pt) * 4;
+      const T psip = T(ps[0]);
+      const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
+      const T* ut = s_nut + (2 * D + s) * 3;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        up[c] = -um[c];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gp[c][k] = gm[c][k];
+        tr[1][c] += psip * ut[c];
+        tr[1][3 + c] += ut[c] * gpp[D];
       }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        up[c] = tr[1][c][0];
-        gp[c][T1] = tr[1][c][1];
-        gp[c][T2] = tr[1][c][2];
-        gp[c][D] = tr[1][c][3];
-      }
-      if (nb[s].enr_nb >= 0) {
-        const double* ps =
-            M.psi + ((size_t)nb[s].enr_nb * M.psi_pts + M.psi_off[1 + 2 * D + (1 - s)] + pt) * 4;
-        const T psip = T(ps[0]);
-        const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T ut = s_nut[(2 * D + s) * 3 + c];
-          up[c] += psip * ut;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) gp[c][k] += ut * gpp[k];
-        }
-      }
+      tr[1][6] += ut[D] * gpp[T1];
+      tr[1][7] += ut[D] * gpp[T2];
     }
     // n = sg e_D
-    const T unm = sg * um[D], unp = sg * up[D];
+    const T unm = sg * tr[0][D], unp = sg * tr[1][D];
     const T am = unm < 0 ? -unm : unm, ap = unp < 0 ? -unp : unp;
     const T lam = T(2) * (am > ap ? am : ap);
     const T wf = T(w1[q1]) * T(w2[q2]) * ht1 * ht2;
-    const T tau = tauF[s];
+    const T tau = s ? tau1 : tau0;
     T jmp[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) jmp[c] = um[c] - up[c];
-    T* fo = fl + s * 12 * FP + pt;
+    for (int c = 0; c < 3; ++c) jmp[c] = tr[0][c] - tr[1][c];
+    T* fo = fl + s * 8 * FP + pt;
+    const T hth = T(0.5) * theta * nu * sg;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      // {{2 nu eps(u)}} n = nu/2 (grad u- + grad u-^T + grad u+ + grad u+^T) n
-      const T visc = (gm[c][D] + gm[D][c] + gp[c][D] + gp[D][c]) * sg;
-      const T fv = T(0.5) * (um[c] * unm + up[c] * unp) + T(0.5) * lam * jmp[c] - T(0.5) * nu * visc +
+      // (grad u + grad u^T) e_D, component c, both sides
+      T sym;
+      if (c == D)
+        sym = T(2) * (tr[0][3 + D] + tr[1][3 + D]);
+      else if (c == T1)
+        sym = tr[0][3 + c] + tr[0][6] + tr[1][3 + c] + tr[1][6];
+      else
+        sym = tr[0][3 + c] + tr[0][7] + tr[1][3 + c] + tr[1][7];
+      const T fv = T(0.5) * (tr[0][c] * unm + tr[1][c] * unp) + T(0.5) * lam * jmp[c] - T(0.5) * nu * sym * sg +
                    tau * nu * jmp[c];
+      // F_g[c][D] = -theta nu/2 (jmp_c + delta_cD jmp_D) sg
+      const T Fn = (c == D) ? -T(2) * hth * jmp[D] : -hth * jmp[c];
       fo[c * FP] = wf * fv;
-      if (ENR) rt[c] += wf * psim * fv;
+      fo[(3 + c) * FP] = wf * Fn;
+      if (ENR) rt[c] += wf * (psim * fv + Fn * gpsim[D]);
     }
-    // F_g[c][k] = -theta nu/2 (jmp_c n_k + jmp_k n_c)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const T nk = (k == D) ? sg : T(0), nc = (c == D) ? sg : T(0);
-        const T Fg = -theta * nu * T(0.5) * (jmp[c] * nk + jmp[k] * nc);
-        fo[(3 + 3 * c + k) * FP] = wf * Fg;
-        if (ENR) rt[c] += wf * Fg * gpsim[k];
-      }
+    // F_g[D][T1] = -theta nu/2 jmp_T1 sg,  F_g[D][T2] = -theta nu/2 jmp_T2 sg
+    const T Ft1 = -hth * jmp[T1], Ft2 = -hth * jmp[T2];
+    fo[6 * FP] = wf * Ft1;
+    fo[7 * FP] = wf * Ft2;
+    if (ENR) rt[D] += wf * (Ft1 * gpsim[T1] + Ft2 * gpsim[T2]);
   }
   __syncthreads();
 
-  // Phase D1: transposed sweep along t2 (q2 -> i2)
-  for (int t = tid; t < 2 * 3 * Q1 * NP; t += nt) {
+  // Phase D1: transposed sweep along t2 (q2 -> i2):
+  //   value test a0 = S2^T fv_c (+ Sd2^T F[D][T2]/ht2 for c = D),
+  //   t1-derivative test a1 = S2^T F[D][T1] (c = D only),
+  //   normal-derivative test a3 = S2^T F[c][D]
+  for (int t = tid; t < 2 * 3 * QN; t += nt) {
     const int i2 = t % NP;
     int r = t / NP;
     const int q1 = r % Q1;
     r /= Q1;
     const int c = r % 3, s = r / 3;
-    const T* fo = fl + s * 12 * FP;
-    const T* fv = fo + c * FP;
-    const T* ft1 = fo + (3 + 3 * c + T1) * FP;
-    const T* ft2 = fo + (3 + 3 * c + T2) * FP;
-    const T* fnn = fo + (3 + 3 * c + D) * FP;
+    const T* fo = fl + s * 8 * FP + q1;
     T a0 = 0, a1 = 0, a3 = 0;
 #pragma unroll
     for (int q2 = 0; q2 < Q2; ++q2) {
-      const int pt = q1 + Q1 * q2;
-      const T b2 = T(S2[q2 * NP + i2]), bd2 = T(Sd2[q2 * NP + i2]);
-      a0 += b2 * fv[pt] + bd2 * ft2[pt] / ht2;
-      a1 += b2 * ft1[pt];
-      a3 += b2 * fnn[pt];
+      const T b2 = T(S2[q2 * NP + i2]);
+      a0 += b2 * fo[c * FP + Q1 * q2];
+      a3 += b2 * fo[(3 + c) * FP + Q1 * q2];
+      if (c == D) {
+        a0 += T(Sd2[q2 * NP + i2]) / ht2 * fo[7 * FP + Q1 * q2];
+        a1 += b2 * fo[6 * FP + Q1 * q2];
+      }
     }
-    T* o = B1 + ((s * 3 + c) * 3) * (Q1 * NP) + q1 * NP + i2;
+    T* o = B1 + ((s * 3 + c) * 3) * QN + q1 * NP + i2;
     o[0] = a0;
-    o[Q1 * NP] = a1;
-    o[2 * Q1 * NP] = a3;
+    o[QN] = a1;
+    o[2 * QN] = a3;
   }
   __syncthreads();
 
@@ -351,13 +362,14 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     T rv[2], bn[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const T* b = B1 + ((s * 3 + c) * 3) * (Q1 * NP) + i2;
+      const T* b = B1 + ((s * 3 + c) * 3) * QN + i2;
       T v = 0, n = 0;
 #pragma unroll
       for (int q1 = 0; q1 < Q1; ++q1) {
-        const T a = T(S1[q1 * NP + i1]), ad = T(Sd1[q1 * NP + i1]);
-        v += a * b[q1 * NP] + ad * b[Q1 * NP + q1 * NP] / ht1;
-        n += a * b[2 * Q1 * NP + q1 * NP];
+        const T a = T(S1[q1 * NP + i1]);
+        v += a * b[q1 * NP];
+        if (c == D) v += T(Sd1[q1 * NP + i1]) / ht1 * b[QN + q1 * NP];
+        n += a * b[2 * QN + q1 * NP];
       }
       rv[s] = v;
       bn[s] = n / hd;
@@ -377,7 +389,7 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
 }
 
 template <typename T, int NP, int NQ, int NQY, bool ENR>
-__global__ __launch_bounds__(256) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
+__global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
                                                   int layer_lo, int nlayers) {
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr TabLayout L = tab_layout(NP, NQ, NQY);
@@ -388,6 +400,7 @@ __global__ __launch_bounds__(256) void vel_kernel(const MeshDev M, const T* __re
   __shared__ T s_ut[3];
   __shared__ T s_nut[18];
   __shared__ T s_red[3 * 4];
+  __shared__ T s_tab[FaceTab<NP, NQ, NQY>::size];
   const int tid = threadIdx.x, nt = blockDim.x;
 
   const int b = blockIdx.x;
@@ -408,6 +421,8 @@ __global__ __launch_bounds__(256) void vel_kernel(const MeshDev M, const T* __re
   const T hx = T(M.hx), hz = T(M.hz), hy = T(M.hy[ey]);
 
   const double* tab = M.tab;
+  // volume sweep matrices: uniform compile-time indices, read through the
+  // scalar cache
   const double* Sx = tab + L.S;
   const double* Dx = tab + L.D;
   const double* wx = tab + L.w;
@@ -417,6 +432,7 @@ __global__ __launch_bounds__(256) void vel_kernel(const MeshDev M, const T* __re
 
   for (int i = tid; i < 3 * NP3; i += nt) s_u[i] = u[e * 3 * NP3 + i];
   if (ENR && tid < 3) s_ut[tid] = u[M.enr_off + enr * 3 + tid];
+  load_face_tab<T, NP, NQ, NQY, ENR>(tab, s_tab);
   __syncthreads();
 
   T* s_val = s_big;             // [c][pt]
@@ -500,9 +516,12 @@ __global__ __launch_bounds__(256) void vel_kernel(const MeshDev M, const T* __re
   T* s_face = s_big + Sh::NL;
   load_neighbour_layers<T, NP>(M, u, s_nl, s_nut, tab + L.nd0, tab + L.nd1, ex, ey, ez, true);
   __syncthreads();
-  vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
-  vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
-  vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
+  vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy, hz,
+                                          rt);
+  vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy, hz,
+                                          rt);
+  vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy, hz,
+                                          rt);
 
   for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
   if (ENR) {
