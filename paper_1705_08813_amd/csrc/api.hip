@@ -1,5 +1,6 @@
 // C ABI entry points: argument checking, mesh set-up on the host, workspace
 // layout, and dispatch to the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -15,7 +16,7 @@ thread_local std::string g_err;
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 struct WsLayout {
-  size_t eta, hy, tab_u, tab_p, tau, psi, diag, diag32, total;
+  size_t eta, hy, tab_u, tab_p, tau, psi, diag, diag32, geo, meas, tauF, wdist, total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -47,7 +48,8 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
     return set_error(DG_ERR_ARG, "geometry or material parameter invalid");
   if (!(P.ip_factor_u > 0) || !(P.ip_factor_p > 0) || !(P.wall_ip_mult > 0))
     return set_error(DG_ERR_ARG, "penalty factors must be positive");
-  if (P.wall_amp != 0.0) return set_error(DG_ERR_UNSUPPORTED, "curved walls are not supported by this build");
+  if (P.wall_amp != 0.0 && P.fully_periodic) return set_error(DG_ERR_ARG, "a curved wall needs walls");
+  if (!(std::fabs(P.wall_amp) < 0.9)) return set_error(DG_ERR_ARG, "wall amplitude must be below 0.9");
   m.P = P;
   m.ncell = (int64_t)P.nx * P.ny * P.nz;
   m.np_u = P.k_u + 1;
@@ -65,6 +67,8 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
   m.psi_pts = psi_points(P.nq_u, P.nq_wn);
   m.hx = P.Lx / P.nx;
   m.hz = P.Lz / P.nz;
+  m.curved = P.wall_amp != 0.0;
+  m.geo_stride = m.curved ? psi_points(P.nq_u, std::max(P.nq_u, P.nq_wn)) : 0;
   const int nqw_eff = m.nenr > 0 ? P.nq_wn : -1;
   if (m.nenr > 0 && !velocity_supported(m.np_u, P.nq_u, nqw_eff))
     return set_error(DG_ERR_UNSUPPORTED, std::string("velocity (k_u+1, nq_u, nq_wn) not compiled; have ") +
@@ -94,6 +98,10 @@ WsLayout layout(const dg_mesh& m) {
   L.psi = o; o = up256(o + sizeof(double) * 4 * (size_t)m.nenr * m.psi_pts);
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
   L.diag32 = o; o = up256(o + sizeof(float) * m.n_p);
+  L.geo = o; o = up256(o + sizeof(double) * 10 * (size_t)m.ncell * m.geo_stride);
+  L.meas = o; o = up256(o + sizeof(double) * (m.curved ? 7 * (size_t)m.ncell : 0));
+  L.tauF = o; o = up256(o + sizeof(double) * (m.curved ? 6 * (size_t)m.ncell : 0));
+  L.wdist = o; o = up256(o + sizeof(double) * (m.curved ? 2 * (size_t)(m.P.nx + 1) : 0));
   L.total = o;
   return L;
 }
@@ -155,6 +163,12 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   m->psi = reinterpret_cast<double*>(base + W.psi);
   m->diag = reinterpret_cast<double*>(base + W.diag);
   m->diag32 = reinterpret_cast<float*>(base + W.diag32);
+  if (m->curved) {
+    m->geo = reinterpret_cast<double*>(base + W.geo);
+    m->meas = reinterpret_cast<double*>(base + W.meas);
+    m->tauF = reinterpret_cast<double*>(base + W.tauF);
+    m->wdist = reinterpret_cast<double*>(base + W.wdist);
+  }
 
   const dg_mesh_params& P = m->P;
   // wall-normal vertices: tanh grading (paper Sec. 5.1)
@@ -185,8 +199,30 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   if (!rc) rc = check_hip(hipMemcpyAsync(m->tab_u, tu.data(), sizeof(double) * tu.size(), hipMemcpyHostToDevice, s), "copy");
   if (!rc) rc = check_hip(hipMemcpyAsync(m->tab_p, tp.data(), sizeof(double) * tp.size(), hipMemcpyHostToDevice, s), "copy");
   if (!rc) rc = check_hip(hipMemcpyAsync(m->tau, tau.data(), sizeof(double) * tau.size(), hipMemcpyHostToDevice, s), "copy");
+  // curved wall: distances of the wall-adjacent vertex rows to the closest
+  // wall vertex (paper Sec. 3.2: y_B is the distance to the closest wall node)
+  std::vector<double> wd;
+  if (m->curved) {
+    const double hx = m->hx, amp = P.wall_amp, Lx = P.Lx;
+    auto yw = [&](double x) { return -1.0 + amp * std::cos(2.0 * M_PI * x / Lx); };
+    auto ymap = [&](double x, double et) { return yw(x) + 0.5 * (et + 1.0) * (1.0 - yw(x)); };
+    wd.assign(2 * (P.nx + 1), 0.0);
+    for (int ix = 0; ix <= P.nx; ++ix) {
+      const double x = ix * hx, y = ymap(x, eta[1]);
+      double best = 1e300;
+      for (int jx = 0; jx < P.nx; ++jx)
+        for (int img = -1; img <= 1; ++img) {
+          const double dx = x - (jx * hx + img * Lx), dy = y - yw(jx * hx);
+          best = std::min(best, std::sqrt(dx * dx + dy * dy));
+        }
+      wd[ix] = best;
+      wd[P.nx + 1 + ix] = std::fabs(1.0 - ymap(x, eta[P.ny - 1]));
+    }
+    if (!rc) rc = check_hip(hipMemcpyAsync(m->wdist, wd.data(), sizeof(double) * wd.size(), hipMemcpyHostToDevice, s), "copy");
+    if (!rc) rc = launch_geometry(m, s);
+  }
   if (!rc) rc = launch_psi(m, s);
-  if (!rc) rc = launch_poisson_diag(m, s);
+  if (!rc && !m->curved) rc = launch_poisson_diag(m, s);
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "setup synchronize");
   if (rc) {
     delete m;
@@ -229,6 +265,7 @@ int dg_apply_velocity_residual(const dg_mesh* m, dg_prec prec, const void* u, vo
 
 int dg_apply_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, void* stream) {
   if (!m || !p || !y) return set_error(DG_ERR_ARG, "mesh/p/y is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Poisson operator is built for flat (box) meshes only");
   if (prec != DG_F64 && prec != DG_F32) return set_error(DG_ERR_ARG, "unknown precision");
   if (p == y) return set_error(DG_ERR_ARG, "p and y must not alias");
   if (!aligned256(p) || !aligned256(y)) return set_error(DG_ERR_ARG, "p and y must be 256-byte aligned");
@@ -237,6 +274,7 @@ int dg_apply_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, voi
 
 int dg_poisson_diagonal(const dg_mesh* m, double* d, void* stream) {
   if (!m || !d) return set_error(DG_ERR_ARG, "mesh/d is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Poisson operator is built for flat (box) meshes only");
   return check_hip(hipMemcpyAsync(d, m->diag, sizeof(double) * m->n_p, hipMemcpyDeviceToDevice,
                                   static_cast<hipStream_t>(stream)),
                    "diagonal copy");

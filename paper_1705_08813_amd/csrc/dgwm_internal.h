@@ -90,6 +90,13 @@ struct dg_mesh {
   float* diag32;          // Poisson diagonal (FP32 copy)
   double* hy;             // ny cell heights
   double lam_max = 0.0;   // cached largest eigenvalue estimate of D^{-1} A (solver)
+  // curved lower wall (wall_amp != 0)
+  int curved = 0;
+  int geo_stride = 0;     // points per cell in the geometry table
+  double* geo = nullptr;  // [cell][geo_stride][J^{-1} (9), weight]
+  double* meas = nullptr; // [cell][volume, six face areas]
+  double* tauF = nullptr; // [cell][face] interior-penalty parameters
+  double* wdist = nullptr; // [2][nx+1] distances to the wall of the vertex rows iy = 1 and iy = ny-1
 };
 
 namespace dgwm {
@@ -100,6 +107,7 @@ int check_hip(hipError_t e, const char* what);
 
 // Launchers (defined next to their kernels).  Return DG_OK or an error code.
 int launch_psi(const dg_mesh* m, hipStream_t s);
+int launch_geometry(const dg_mesh* m, hipStream_t s);
 int launch_poisson_diag(const dg_mesh* m, hipStream_t s);
 int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);

@@ -23,6 +23,11 @@ struct MeshDev {
   double pen;         // ip_factor (k+1)^2
   double wall_mult;
   int64_t enr_off;    // start of the enrichment block in the velocity vector
+  // curved geometry (nullptr for affine box cells)
+  const double* geo;  // [cell][geo_stride][J^{-1} (9), weight]
+  int geo_stride;
+  const double* tauF; // [cell][face]
+  int nq_wn;          // wall-normal points of enriched cells (the point layout of their tables)
 };
 
 // Enriched index of cell (ex, ey, ez) or -1.

@@ -44,10 +44,15 @@ __device__ void spalding_root(double yp, double kappa, double B, double& U, doub
 
 // pts: the NQ Gauss points of the wall-parallel rule followed by the NQY
 // points of the wall-normal rule (on [0,1]).
+// Curved lower wall: y_h is the bilinear (x, eta) interpolation of the vertex
+// distances to the closest wall vertex (wdist: rows iy = 1 and iy = ny-1; the
+// wall rows are 0), grad y_h = J^{-T} grad_xi y_h with J^{-1} from the
+// geometry table at the same point.
 template <int NQ, int NQY>
 __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, const double* __restrict__ eta,
                            const double* __restrict__ pts, const double* __restrict__ tau, double nu, double kappa,
-                           double B, int64_t nenr, int psi_pts, double* __restrict__ psi) {
+                           double B, int64_t nenr, int psi_pts, double* __restrict__ psi,
+                           const double* __restrict__ geo, int geo_stride, const double* __restrict__ wdist) {
   constexpr int NPTS = NQ * NQY * NQ;
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gid >= nenr * psi_pts) return;
@@ -60,11 +65,12 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
   const bool lower = (slot == lower_slot);
   const int ey = lower ? 0 : ny - 1;
   const double* gy = pts + NQ;
-  // wall-normal reference coordinate of the point and its tau column
-  double xiy;
+  // reference coordinates (x, wall-normal) of the point and its tau column
+  double xiy, xix;
   int qx, qz;
   if (pt < NPTS) {
     qx = pt % NQ;
+    xix = pts[qx];
     xiy = gy[(pt / NQ) % NQY];
     qz = pt / (NQ * NQY);
   } else {
@@ -78,21 +84,38 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
     const int q1 = k % Q1, q2 = k / Q1;
     if (d == 0) {
       qx = s ? NQ - 1 : 0;
+      xix = (double)s;
       xiy = gy[q1];
       qz = q2;
     } else if (d == 1) {
       qx = q1;
+      xix = pts[q1];
       xiy = (double)s;
       qz = q2;
     } else {
       qx = q1;
+      xix = pts[q1];
       xiy = gy[q2];
       qz = s ? NQ - 1 : 0;
     }
   }
-  const double y = eta[ey] + (eta[ey + 1] - eta[ey]) * xiy;
-  const double yh = lower ? y + 1.0 : 1.0 - y;
-  const double dyh = lower ? 1.0 : -1.0;
+  double yh, gyh[3];
+  if (!geo) {
+    const double y = eta[ey] + (eta[ey + 1] - eta[ey]) * xiy;
+    yh = lower ? y + 1.0 : 1.0 - y;
+    gyh[0] = 0.0;
+    gyh[1] = lower ? 1.0 : -1.0;
+    gyh[2] = 0.0;
+  } else {
+    const double d00 = lower ? 0.0 : wdist[nx + 1 + ex], d10 = lower ? 0.0 : wdist[nx + 1 + ex + 1];
+    const double d01 = lower ? wdist[ex] : 0.0, d11 = lower ? wdist[ex + 1] : 0.0;
+    const double bot = (1.0 - xix) * d00 + xix * d10, top = (1.0 - xix) * d01 + xix * d11;
+    yh = (1.0 - xiy) * bot + xiy * top;
+    const double gx = (1.0 - xiy) * (d10 - d00) + xiy * (d11 - d01), gyy = top - bot;
+    const int64_t e = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+    const double* Ji = geo + (e * geo_stride + pt) * 10;
+    for (int dd = 0; dd < 3; ++dd) gyh[dd] = gx * Ji[0 * 3 + dd] + gyy * Ji[1 * 3 + dd];
+  }
   const int w = lower ? 0 : 1;
   const double tw = tau[(((int64_t)w * nz + ez) * nx + ex) * NQ * NQ + (int64_t)qz * NQ + qx];
   double* o = psi + gid * 4;
@@ -104,9 +127,9 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
   double U, dU;
   spalding_root(fmax(yh, 0.0) * st, kappa, B, U, dU);
   o[0] = U;
-  o[1] = 0.0;
-  o[2] = dU * st * dyh;
-  o[3] = 0.0;
+  o[1] = dU * st * gyh[0];
+  o[2] = dU * st * gyh[1];
+  o[3] = dU * st * gyh[2];
 }
 
 }  // namespace
@@ -124,7 +147,7 @@ int launch_psi(const dg_mesh* m, hipStream_t s) {
   if (m->P.nq_u == a && m->P.nq_wn == b) {                                                                   \
     hipLaunchKernelGGL((psi_kernel<a, b>), dim3(nb), dim3(128), 0, s, m->P.nx, m->P.ny, m->P.nz, lower_slot, \
                        m->n_enr_layers, m->eta, pts, m->tau, m->P.nu, m->P.kappa, m->P.B, m->nenr,          \
-                       m->psi_pts, m->psi);                                                                  \
+                       m->psi_pts, m->psi, m->geo, m->geo_stride, m->wdist);                                 \
     return check_hip(hipGetLastError(), "psi kernel launch");                                                \
   }
   DG_PSI_COMBOS(X)

@@ -30,8 +30,13 @@ struct VelShape {
   static constexpr int FL = 2 * 8 * FMAX;               // fluxes [s][field][pt]
   static constexpr int B1 = 2 * 3 * 3 * Q1MAX * NP;     // t2-transposed tests [s][c][3][q1][i2]
   static constexpr int FACE = NL + LAYO + A1 + FL + B1;
+  // curved cells: 12 trace fields per side and reference-gradient tests
+  static constexpr int A1C = 2 * 2 * 3 * 3 * Q1MAX * NP;
+  static constexpr int FLC = 2 * 12 * FMAX;
+  static constexpr int FACEC = NL + LAYO + A1C + FLC + B1;
   static constexpr int VOL = 12 * NPTS;
-  static constexpr int BIG = VOL > FACE ? VOL : FACE;
+  static constexpr int BIG0 = VOL > FACE ? VOL : FACE;
+  static constexpr int BIG = BIG0 > FACEC ? BIG0 : FACEC;
 };
 
 // Node index of the point at position l along direction D on the line
@@ -77,7 +82,7 @@ __device__ __forceinline__ FaceNb face_nb(const MeshDev& M, int ex, int ey, int 
 // Neighbour face layers of all six faces: value and normal derivative of each
 // component on the neighbour's node layer at the shared face.  One global
 // read per neighbour node; all six faces are fetched in one phase.
-template <typename T, int NP>
+template <typename T, int NP, bool REF>
 __device__ __forceinline__ void load_neighbour_layers(const MeshDev& M, const T* __restrict__ u, T* s_nl, T* s_nut,
                                                       const double* tab_nd0, const double* tab_nd1, int ex, int ey,
                                                       int ez, bool need_nut) {
@@ -100,8 +105,10 @@ __device__ __forceinline__ void load_neighbour_layers(const MeshDev& M, const T*
 #pragma unroll
       for (int l = 0; l < NP; ++l) der += T(nd[l]) * x[l];
       val = x[lface];
-      const T hdn = D == 0 ? T(M.hx) : (D == 1 ? T(M.hy[nb.nidx1]) : T(M.hz));
-      der /= hdn;
+      if (!REF) {  // affine cells: physical normal derivative
+        const T hdn = D == 0 ? T(M.hx) : (D == 1 ? T(M.hy[nb.nidx1]) : T(M.hz));
+        der /= hdn;
+      }
     }
     s_nl[((f * 3 + c) * 2 + 0) * NP2 + k] = val;
     s_nl[((f * 3 + c) * 2 + 1) * NP2 + k] = der;
@@ -388,7 +395,252 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   __syncthreads();
 }
 
-template <typename T, int NP, int NQ, int NQY, bool ENR>
+// Curved cells: both faces of direction D with general normals.  Traces carry
+// the full reference gradient (12 fields per side), mapped with the stored
+// J^{-1} of each side at the face point; the gradient tests are pulled back
+// to reference derivatives with the own side's J^{-1}.
+template <typename T, int NP, int NQ, int NQY, bool ENR, int D>
+__device__ __forceinline__ void vel_faces_dir_curved(const MeshDev& M, int64_t e, const T* s_u, const T* s_nl,
+                                                     const T* s_nut, T* s_r, T* s_face, const T* s_ut,
+                                                     const T* s_tab, int ex, int ey, int ez, int64_t enr, T rt[3]) {
+  using Sh = VelShape<T, NP, NQ, NQY>;
+  constexpr int T1 = D == 0 ? 1 : 0;
+  constexpr int T2 = D == 2 ? 1 : 2;
+  constexpr int Q1 = T1 == 1 ? NQY : NQ;
+  constexpr int Q2 = T2 == 1 ? NQY : NQ;
+  constexpr int FP = Q1 * Q2;
+  constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3;
+  constexpr int QN = Q1 * NP;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  using TL = FaceTab<NP, NQ, NQY>;
+  const T* S1 = s_tab + (T1 == 1 ? TL::Sy : TL::Sq);
+  const T* Sd1 = s_tab + (T1 == 1 ? TL::Sdy : TL::Sdq);
+  const T* S2 = s_tab + (T2 == 1 ? TL::Sy : TL::Sq);
+  const T* Sd2 = s_tab + (T2 == 1 ? TL::Sdy : TL::Sdq);
+  const T* nd0 = s_tab + TL::nd0;
+  const T* nd1 = s_tab + TL::nd1;
+
+  T* lay = s_face;                 // [s][c][val|d_n][NP2]
+  T* A1 = lay + Sh::LAYO;          // [s][side][c][Sv|Sdv|Sn][q1][i2]
+  T* fl = A1 + Sh::A1C;            // [s][12][pt]
+  T* B1 = fl + Sh::FLC;            // [s][c][value|t1|normal][q1][i2]
+
+  const FaceNb nb0 = face_nb(M, ex, ey, ez, D, 0), nb1 = face_nb(M, ex, ey, ez, D, 1);
+  const bool wall0 = nb0.wall, wall1 = nb1.wall;
+
+  for (int t = tid; t < 2 * 3 * NP2; t += nt) {
+    const int s = t / (3 * NP2), rem = t - s * 3 * NP2;
+    const int c = rem / NP2, k = rem - c * NP2;
+    int base, stride;
+    line_of<NP>(D, k % NP, k / NP, base, stride);
+    const T* nd = s ? nd1 : nd0;
+    const T* src = s_u + c * NP3 + base;
+    T der = 0;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) der += nd[l] * src[l * stride];
+    lay[((s * 3 + c) * 2 + 0) * NP2 + k] = src[(s ? NP - 1 : 0) * stride];
+    lay[((s * 3 + c) * 2 + 1) * NP2 + k] = der;
+  }
+  __syncthreads();
+
+  for (int t = tid; t < 2 * 2 * 3 * 3 * QN; t += nt) {
+    const int q1 = t % Q1;
+    int r = t / Q1;
+    const int i2 = r % NP;
+    r /= NP;
+    const int f = r % 3;
+    r /= 3;
+    const int c = r % 3;
+    r /= 3;
+    const int side = r % 2, s = r / 2;
+    if (side == 1 && (s ? wall1 : wall0)) continue;
+    const T* lv = (side == 0 ? lay + ((s * 3 + c) * 2) * NP2 : s_nl + (((2 * D + s) * 3 + c) * 2) * NP2) +
+                  (f == 2 ? NP2 : 0) + NP * i2;
+    const T* mat = (f == 1 ? Sd1 : S1) + q1 * NP;
+    T acc = 0;
+#pragma unroll
+    for (int i1 = 0; i1 < NP; ++i1) acc += mat[i1] * lv[i1];
+    A1[((((s * 2 + side) * 3 + c) * 3 + f) * Q1 + q1) * NP + i2] = acc;
+  }
+  __syncthreads();
+
+  const T nu = T(M.nu), theta = T(M.theta);
+  const int nqy_own = ENR ? NQY : NQ;
+  for (int t = tid; t < 2 * FP; t += nt) {
+    const int s = t / FP, pt = t - s * FP;
+    const int q1 = pt % Q1, q2 = pt / Q1;
+    const T sg = s ? T(1) : T(-1);
+    const bool wall = s ? wall1 : wall0;
+    const FaceNb& nb = s ? nb1 : nb0;
+    const int f = 2 * D + s, fn = 2 * D + (1 - s);
+    const double* go = M.geo + (e * M.geo_stride + psi_face_offset(NQ, nqy_own, f) + pt) * 10;
+    T Jo[3][3], Jn[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Jo[a][d] = T(go[3 * a + d]);
+    const T wf = T(go[9]);
+    T um[3], up[3], gm[3][3], gp[3][3];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 1 && wall) continue;
+      if (side == 1) {
+        const int nqy_nb = nb.enr_nb >= 0 ? M.nq_wn : NQ;  // the neighbour's own point layout
+        const double* gn = M.geo + (nb.enb * M.geo_stride + psi_face_offset(NQ, nqy_nb, fn) + pt) * 10;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Jn[a][d] = T(gn[3 * a + d]);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T* a = A1 + (((s * 2 + side) * 3 + c) * 3) * QN + q1 * NP;
+        T v = 0, d1 = 0, d2 = 0, dn = 0;
+#pragma unroll
+        for (int i2 = 0; i2 < NP; ++i2) {
+          const T b2 = S2[q2 * NP + i2], bd2 = Sd2[q2 * NP + i2];
+          v += b2 * a[i2];
+          d1 += b2 * a[QN + i2];
+          d2 += bd2 * a[i2];
+          dn += b2 * a[2 * QN + i2];
+        }
+        T gr[3];
+        gr[T1] = d1;
+        gr[T2] = d2;
+        gr[D] = dn;
+        T* uo = side == 0 ? um : up;
+        T(*go3)[3] = side == 0 ? gm : gp;
+        uo[c] = v;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const T(*Jx)[3] = side == 0 ? Jo : Jn;
+          go3[c][d] = gr[0] * Jx[0][d] + gr[1] * Jx[1][d] + gr[2] * Jx[2][d];
+        }
+      }
+    }
+    T psim = 0, gpsim[3] = {0, 0, 0};
+    if (ENR) {
+      const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + f] + pt) * 4;
+      psim = T(ps[0]);
+      gpsim[0] = T(ps[1]);
+      gpsim[1] = T(ps[2]);
+      gpsim[2] = T(ps[3]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        um[c] += psim * s_ut[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gm[c][k] += s_ut[c] * gpsim[k];
+      }
+    }
+    if (wall) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        up[c] = -um[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gp[c][k] = gm[c][k];
+      }
+    } else if (nb.enr_nb >= 0) {
+      const double* ps = M.psi + ((size_t)nb.enr_nb * M.psi_pts + M.psi_off[1 + fn] + pt) * 4;
+      const T psip = T(ps[0]);
+      const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
+      const T* ut = s_nut + f * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        up[c] += psip * ut[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gp[c][k] += ut[c] * gpp[k];
+      }
+    }
+    T nv[3];
+    {
+      const T nr = sqrt(Jo[D][0] * Jo[D][0] + Jo[D][1] * Jo[D][1] + Jo[D][2] * Jo[D][2]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) nv[d] = sg * Jo[D][d] / nr;
+    }
+    const T tau = T(M.tauF[e * 6 + f]);
+    const T unm = um[0] * nv[0] + um[1] * nv[1] + um[2] * nv[2];
+    const T unp = up[0] * nv[0] + up[1] * nv[1] + up[2] * nv[2];
+    const T am = unm < 0 ? -unm : unm, ap = unp < 0 ? -unp : unp;
+    const T lam = T(2) * (am > ap ? am : ap);
+    T jmp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) jmp[c] = um[c] - up[c];
+    T* fo = fl + s * 12 * FP + pt;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T visc = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) visc += (gm[c][k] + gm[k][c] + gp[c][k] + gp[k][c]) * nv[k];
+      const T fv = T(0.5) * (um[c] * unm + up[c] * unp) + T(0.5) * lam * jmp[c] - T(0.5) * nu * visc +
+                   tau * nu * jmp[c];
+      T F[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) F[k] = -theta * nu * T(0.5) * (jmp[c] * nv[k] + jmp[k] * nv[c]);
+      T Fr[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) Fr[a] = F[0] * Jo[a][0] + F[1] * Jo[a][1] + F[2] * Jo[a][2];
+      fo[c * FP] = wf * fv;
+      fo[(3 + c) * FP] = wf * Fr[T1];
+      fo[(6 + c) * FP] = wf * Fr[T2];
+      fo[(9 + c) * FP] = wf * Fr[D];
+      if (ENR) rt[c] += wf * (psim * fv + F[0] * gpsim[0] + F[1] * gpsim[1] + F[2] * gpsim[2]);
+    }
+  }
+  __syncthreads();
+
+  for (int t = tid; t < 2 * 3 * QN; t += nt) {
+    const int i2 = t % NP;
+    int r = t / NP;
+    const int q1 = r % Q1;
+    r /= Q1;
+    const int c = r % 3, s = r / 3;
+    const T* fo = fl + s * 12 * FP + q1;
+    T a0 = 0, a1 = 0, a3 = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < Q2; ++q2) {
+      const T b2 = S2[q2 * NP + i2], bd2 = Sd2[q2 * NP + i2];
+      a0 += b2 * fo[c * FP + Q1 * q2] + bd2 * fo[(6 + c) * FP + Q1 * q2];
+      a1 += b2 * fo[(3 + c) * FP + Q1 * q2];
+      a3 += b2 * fo[(9 + c) * FP + Q1 * q2];
+    }
+    T* o = B1 + ((s * 3 + c) * 3) * QN + q1 * NP + i2;
+    o[0] = a0;
+    o[QN] = a1;
+    o[2 * QN] = a3;
+  }
+  __syncthreads();
+
+  for (int t = tid; t < 3 * NP2; t += nt) {
+    const int c = t / NP2, k = t - c * NP2;
+    const int i1 = k % NP, i2 = k / NP;
+    T rv[2], bn[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const T* b = B1 + ((s * 3 + c) * 3) * QN + i2;
+      T v = 0, n = 0;
+#pragma unroll
+      for (int q1 = 0; q1 < Q1; ++q1) {
+        v += S1[q1 * NP + i1] * b[q1 * NP] + Sd1[q1 * NP + i1] * b[QN + q1 * NP];
+        n += S1[q1 * NP + i1] * b[2 * QN + q1 * NP];
+      }
+      rv[s] = v;
+      bn[s] = n;
+    }
+    int base, stride;
+    line_of<NP>(D, i1, i2, base, stride);
+    T* dst = s_r + c * NP3 + base;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      T add = nd0[l] * bn[0] + nd1[l] * bn[1];
+      if (l == 0) add += rv[0];
+      if (l == NP - 1) add += rv[1];
+      dst[l * stride] += add;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
 __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
                                                   int layer_lo, int nlayers) {
   using Sh = VelShape<T, NP, NQ, NQY>;
@@ -419,6 +671,8 @@ __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* _
   }
   const int64_t e = ex + (int64_t)M.nx * (ey + (int64_t)M.ny * ez);
   const T hx = T(M.hx), hz = T(M.hz), hy = T(M.hy[ey]);
+  // sweeps produce physical derivatives on affine cells, reference ones on curved cells
+  const T ix = CURVED ? T(1) : T(1) / hx, iy = CURVED ? T(1) : T(1) / hy, iz = CURVED ? T(1) : T(1) / hz;
 
   const double* tab = M.tab;
   // volume sweep matrices: uniform compile-time indices, read through the
@@ -449,9 +703,9 @@ __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* _
     __syncthreads();
   }
   // gradients by collocation through the Gauss points
-  sweep<0, NQ, NQY, NQ, NQ, false, false>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, Dx, T(1) / hx, 3);
-  sweep<1, NQ, NQY, NQ, NQY, false, false>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, Dy, T(1) / hy, 3);
-  sweep<2, NQ, NQY, NQ, NQ, false, false>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, Dx, T(1) / hz, 3);
+  sweep<0, NQ, NQY, NQ, NQ, false, false>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, Dx, ix, 3);
+  sweep<1, NQ, NQY, NQ, NQY, false, false>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, Dy, iy, 3);
+  sweep<2, NQ, NQY, NQ, NQ, false, false>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, Dx, iz, 3);
   __syncthreads();
 
   // pointwise flux G = 2 nu eps(u) - u (x) u, times the quadrature weight
@@ -460,13 +714,31 @@ __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* _
   const T vol = hx * hy * hz;
   for (int pt = tid; pt < NPTS; pt += nt) {
     const int qx = pt % NQ, qy = (pt / NQ) % NQY, qz = pt / (NQ * NQY);
-    const T wq = T(wx[qx]) * T(wy[qy]) * T(wx[qz]) * vol;
+    T wq, Ji[3][3];
+    if (CURVED) {
+      const double* g = M.geo + (e * M.geo_stride + pt) * 10;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Ji[a][d] = T(g[3 * a + d]);
+      wq = T(g[9]);
+    } else {
+      wq = T(wx[qx]) * T(wy[qy]) * T(wx[qz]) * vol;
+    }
     T uu[3], gg[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       uu[c] = s_val[c * NPTS + pt];
+      if (CURVED) {
+        T gr[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) gg[c][d] = s_grad[(c * 3 + d) * NPTS + pt];
+        for (int a = 0; a < 3; ++a) gr[a] = s_grad[(c * 3 + a) * NPTS + pt];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gg[c][d] = gr[0] * Ji[0][d] + gr[1] * Ji[1][d] + gr[2] * Ji[2][d];
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gg[c][d] = s_grad[(c * 3 + d) * NPTS + pt];
+      }
     }
     T gps[3] = {0, 0, 0};
     if (ENR) {
@@ -483,22 +755,26 @@ __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* _
       }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+      T G[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const T G = wq * (nu * (gg[c][d] + gg[d][c]) - uu[c] * uu[d]);
-        s_grad[(c * 3 + d) * NPTS + pt] = G;
-        if (ENR) rt[c] += G * gps[d];
+        G[d] = wq * (nu * (gg[c][d] + gg[d][c]) - uu[c] * uu[d]);
+        if (ENR) rt[c] += G[d] * gps[d];
       }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        s_grad[(c * 3 + a) * NPTS + pt] = CURVED ? G[0] * Ji[a][0] + G[1] * Ji[a][1] + G[2] * Ji[a][2] : G[a];
+    }
   }
   __syncthreads();
 
   // integrate: W = sum_d D_d^T G_d / h_d, then transposed interpolation
-  sweep<0, NQ, NQY, NQ, NQ, true, false>(s_grad + 0 * NPTS, 3 * NPTS, s_val, NPTS, Dx, T(1) / hx, 3);
+  sweep<0, NQ, NQY, NQ, NQ, true, false>(s_grad + 0 * NPTS, 3 * NPTS, s_val, NPTS, Dx, ix, 3);
   __syncthreads();
-  sweep<1, NQ, NQY, NQ, NQY, true, true>(s_grad + 1 * NPTS, 3 * NPTS, s_val, NPTS, Dy, T(1) / hy, 3);
+  sweep<1, NQ, NQY, NQ, NQY, true, true>(s_grad + 1 * NPTS, 3 * NPTS, s_val, NPTS, Dy, iy, 3);
   __syncthreads();
-  sweep<2, NQ, NQY, NQ, NQ, true, true>(s_grad + 2 * NPTS, 3 * NPTS, s_val, NPTS, Dx, T(1) / hz, 3);
+  sweep<2, NQ, NQY, NQ, NQ, true, true>(s_grad + 2 * NPTS, 3 * NPTS, s_val, NPTS, Dx, iz, 3);
   __syncthreads();
   {
     T* tB = s_grad;                       // (NQ, NQY, NP) x 3
@@ -514,14 +790,26 @@ __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* _
   // faces: neighbour layers of all six faces (one phase), then each direction
   T* s_nl = s_big;
   T* s_face = s_big + Sh::NL;
-  load_neighbour_layers<T, NP>(M, u, s_nl, s_nut, tab + L.nd0, tab + L.nd1, ex, ey, ez, true);
+  load_neighbour_layers<T, NP, CURVED>(M, u, s_nl, s_nut, tab + L.nd0, tab + L.nd1, ex, ey, ez, true);
   __syncthreads();
-  vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy, hz,
-                                          rt);
-  vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy, hz,
-                                          rt);
-  vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy, hz,
-                                          rt);
+  if (CURVED)
+    vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 0>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
+                                                 rt);
+  else
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy,
+                                          hz, rt);
+  if (CURVED)
+    vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 1>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
+                                                 rt);
+  else
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy,
+                                          hz, rt);
+  if (CURVED)
+    vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 2>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
+                                                 rt);
+  else
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy,
+                                          hz, rt);
 
   for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
   if (ENR) {
@@ -539,11 +827,18 @@ int launch_vel_t(const dg_mesh* m, const MeshDev& M, const void* u, void* r, hip
   const int nl = hi - lo + 1;
   if (nl > 0) {
     const unsigned nb = (unsigned)((int64_t)m->P.nx * nl * m->P.nz);
-    hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQ, false>), dim3(nb), dim3(256), 0, s, M, uu, rr, lo, nl);
+    if (m->curved)
+      hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQ, false, true>), dim3(nb), dim3(256), 0, s, M, uu, rr, lo, nl);
+    else
+      hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQ, false, false>), dim3(nb), dim3(256), 0, s, M, uu, rr, lo, nl);
   }
   if (m->nenr > 0) {
-    hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQW, true>), dim3((unsigned)m->nenr), dim3(256), 0, s, M, uu, rr,
-                       0, 0);
+    if (m->curved)
+      hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQW, true, true>), dim3((unsigned)m->nenr), dim3(256), 0, s, M, uu,
+                         rr, 0, 0);
+    else
+      hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQW, true, false>), dim3((unsigned)m->nenr), dim3(256), 0, s, M,
+                         uu, rr, 0, 0);
   }
   return check_hip(hipGetLastError(), "velocity kernel launch");
 }
@@ -569,6 +864,10 @@ MeshDev make_meshdev_u(const dg_mesh* m) {
   M.pen = m->P.ip_factor_u * (m->P.k_u + 1.0) * (m->P.k_u + 1.0);
   M.wall_mult = m->P.wall_ip_mult;
   M.enr_off = m->ncell * 3 * (int64_t)m->np_u * m->np_u * m->np_u;
+  M.geo = m->geo;
+  M.geo_stride = m->geo_stride;
+  M.tauF = m->tauF;
+  M.nq_wn = m->P.nq_wn;
   return M;
 }
 

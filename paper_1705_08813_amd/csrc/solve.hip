@@ -304,6 +304,7 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   if (!(sp->rtol > 0) || sp->cheb_degree < 1 || sp->max_inner < 0 || sp->max_outer < 1)
     return set_error(DG_ERR_ARG, "invalid solve parameters");
   if (b == x) return set_error(DG_ERR_ARG, "b and x must not alias");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Poisson operator is built for flat (box) meshes only");
   Solver S;
   S.m = m;
   S.s = static_cast<hipStream_t>(stream);

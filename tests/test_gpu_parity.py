@@ -44,6 +44,13 @@ VEL_CASES = {
     "k4_lower_only": Workload("k4l", MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=4, nq_u=7, enrich_upper=0), 15, 0.5, 1.5),
     "k3_nonsym": Workload("k3n", MeshConfig(nx=2, ny=3, nz=3, gamma=0.9, k_u=3, nq_u=5, theta=-1.0), 16, 0.5, 1.5),
     "k3_self_periodic": Workload("k3s", MeshConfig(nx=1, ny=2, nz=1, k_u=3, nq_u=4, nq_wn=8), 17, 0.5, 1.5),
+    # curved lower wall y_w = -1 + 0.3 cos(2 pi x/Lx), isoparametric cells, both walls enriched
+    "curved_k3": Workload("c3", MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3),
+                          18, 0.2, 2.0),
+    "curved_k5": Workload("c5", MeshConfig(nx=3, ny=3, nz=2, wall_amp=0.3, k_u=5, nq_u=8, nq_wn=8, k_p=4, nq_p=5),
+                          19, 0.2, 2.0),
+    "curved_k4_stretched": Workload("c4", MeshConfig(nx=3, ny=4, nz=2, gamma=1.2, wall_amp=0.25, k_u=4, nq_u=7,
+                                                     nq_wn=8, enrich_upper=0), 20, 0.5, 1.5),
 }
 
 
@@ -64,7 +71,7 @@ def test_velocity_residual_f64(name):
         assert _rel(re, oe) <= 1e-12, _rel(re, oe)
 
 
-@pytest.mark.parametrize("name", ["tiny", "k4_large_like", "k3_periodic"])
+@pytest.mark.parametrize("name", ["tiny", "k4_large_like", "k3_periodic", "curved_k3"])
 def test_velocity_residual_f32_bound(name):
     wl = VEL_CASES[name]
     _log(f"[gpu] velocity f32 case={name}")
@@ -190,3 +197,35 @@ def test_wall_shear_update_matches_fresh_setup():
     r = mesh.apply_velocity_residual(u).cpu().numpy()
     r_orc = O.velocity_residual(wl.mesh, inp["u"], tau2)
     assert _rel(r, r_orc) <= 1e-12
+
+
+def test_curved_config_sampled():
+    """48x24x24 curved channel, k=5 (8 Gauss points), both walls enriched,
+    tau_w ~ U[0.2, 2]: sampled cells against the oracle, FP64."""
+    wl = PRESETS["curved"]
+    m = wl.mesh
+    _log("[gpu] curved config: setup")
+    inp = draw_inputs(wl, want=("u", "tau"))
+    mesh = Mesh(m, inp["tau"])
+    r = mesh.apply_velocity_residual(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    rng = np.random.default_rng(8)
+    nx, ny, nz = m.nx, m.ny, m.nz
+    cells = set(rng.integers(0, m.ncell, 60).tolist())
+    for ey in (0, 1, ny - 2, ny - 1):
+        for _ in range(15):
+            cells.add(int(rng.integers(0, nx)) + nx * (ey + ny * int(rng.integers(0, nz))))
+    cells = np.array(sorted(cells), dtype=np.int64)
+    _log(f"[gpu] curved config: oracle on {cells.size} cells")
+    r_orc = O.velocity_residual(m, inp["u"], inp["tau"], cells=cells)
+    n3 = (m.k_u + 1) ** 3
+    rows = (cells[:, None] * 3 * n3 + np.arange(3 * n3)[None, :]).ravel()
+    assert _rel(r[rows], r_orc[rows]) <= 1e-12
+    off = m.ncell * 3 * n3
+    enr_rows = []
+    for e in cells:
+        ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+        if ey in (0, ny - 1):
+            k = ex + nx * ((0 if ey == 0 else 1) + 2 * ez)
+            enr_rows += [off + 3 * k + c for c in range(3)]
+    enr_rows = np.array(enr_rows)
+    assert _rel(r[enr_rows], r_orc[enr_rows]) <= 1e-12

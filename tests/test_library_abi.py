@@ -35,7 +35,7 @@ def ws_bytes(cfg):
 
 
 def test_workspace_sizes_and_argument_errors():
-    for name in ("tiny", "large", "precision"):
+    for name in ("tiny", "large", "precision", "curved"):
         assert ws_bytes(PRESETS[name].mesh) > 0
     good = PRESETS["tiny"].mesh
     bad = [good.with_(nx=0), good.with_(ny=1), good.with_(k_u=0), good.with_(nu=-1.0), good.with_(nq_u=40),
