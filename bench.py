@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--solves", type=int, default=5, help="timed Poisson solves per precision (extras)")
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests of the serving stream run after the step timing (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for PMC byte calibration)")
     args = ap.parse_args()
@@ -168,6 +170,7 @@ def main():
               "poisson_hbm_frac_alg": BYTES_PER_DOF_F64 * n_p / t_poi / 1e9 / HBM_PEAK_GBS,
               "kernel_src_sha": kernel_source_hash()}
 
+    print(f"bench: {K} steps in {wall:.3f} s", file=sys.stderr, flush=True)
     if not args.no_extras:
         # FP32 operator applications on the same data
         u32, p32 = u.float(), p.float()
@@ -192,6 +195,7 @@ def main():
                        "velocity_f32_GBps_alg": 8.0 * n_vel / tv32 / 1e9,
                        "poisson_f32_GBps_alg": 8.0 * n_p / tp32 / 1e9})
     if not args.no_extras:
+        print("bench: Poisson solves", file=sys.stderr, flush=True)
         # Poisson solve to 1e-10 (same mesh, k=3): mixed precision vs all-FP64
         bsol = torch.tensor(np.random.default_rng(PRESETS["precision"].seed).uniform(-1, 1, n_p), device=dev)
         for mixed in (True, False):
@@ -213,6 +217,60 @@ def main():
                            "rel_resid": st.rel_resid, "solves": args.solves,
                            "dofs_per_s": n_p / float(np.median(times))}
         extras["solve_speedup_mixed_vs_f64"] = extras["solve_f64"]["median_s"] / extras["solve_mixed"]["median_s"]
+    if not args.no_extras:
+        print("bench: curved configuration", file=sys.stderr, flush=True)
+        # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)
+        wc = PRESETS["curved"]
+        ic = draw_inputs(wc, want=("u", "tau"))
+        cmesh = Mesh(wc.mesh, ic["tau"], device=dev)
+        cu = torch.tensor(ic["u"], device=dev)
+        cr = torch.empty_like(cu)
+        cu32, cr32 = cu.float(), torch.empty(cu.numel(), dtype=torch.float32, device=dev)
+        nrep = max(5, K // 5)
+        times = {}
+        for name, (a, b) in (("f64", (cu, cr)), ("f32", (cu32, cr32))):
+            for _ in range(2):
+                cmesh.apply_velocity_residual(a, b)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(nrep):
+                cmesh.apply_velocity_residual(a, b)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) / nrep * 1e-3
+        cm = wc.mesh
+        pts = cm.nq_u ** 3 + 6 * cm.nq_u * max(cm.nq_u, cm.nq_wn)   # volume + face points per cell
+        geo_b = 10 * 8 * pts * cm.ncell                               # J^-1 and weight, FP64
+        extras["curved"] = {"velocity_dofs": cmesh.n_vel, "velocity_f64_ms": times["f64"] * 1e3,
+                            "velocity_f32_ms": times["f32"] * 1e3,
+                            "f64_dofs_per_s": cmesh.n_vel / times["f64"], "f32_dofs_per_s": cmesh.n_vel / times["f32"],
+                            "alg_bytes_per_dof_f64": (16.0 * cmesh.n_vel + geo_b) / cmesh.n_vel,
+                            "f64_GBps_alg": (16.0 * cmesh.n_vel + geo_b) / times["f64"] / 1e9,
+                            "f32_GBps_alg": (8.0 * cmesh.n_vel + geo_b) / times["f32"] / 1e9}
+        del cmesh, cu, cr, cu32, cr32
+    if not args.no_extras and args.serving_requests > 0:
+        # serving: seeded Poisson-arrival stream of channel instances (grid, k, nu mixed), each 10
+        # velocity-residual applies + one mixed-precision solve to 1e-10; batched velocity rounds
+        from paper_1705_08813_amd.inputs import ServingConfig, serving_requests
+        from paper_1705_08813_amd.serving import Server
+        del mesh
+        torch.cuda.empty_cache()
+        scfg = ServingConfig(n_requests=args.serving_requests)
+        reqs = serving_requests(scfg)
+        print(f"bench: serving {len(reqs)} requests", file=sys.stderr, flush=True)
+        first_of_k = {}
+        for q in reqs:
+            first_of_k.setdefault(q.workload.mesh.k_u, q)
+        # load every kernel once before the timed stream
+        Server(applies=scfg.applies, device=dev).run(list(first_of_k.values()), time_scale=0.0)
+        rep = Server(applies=scfg.applies, device=dev).run(reqs)
+        srv = rep.summary()
+        srv.update({"stream": f"{scfg.n_requests} requests, exponential gaps mean {scfg.mean_interarrival * 1e3:g} ms, "
+                              f"grids {list(scfg.grids)}, k {list(scfg.degrees)}, k_p = k-1, "
+                              f"{scfg.applies} velocity applies + 1 mixed solve (1e-10) each",
+                    "budget_bytes": 32 << 30, "slots": 64})
+        extras["serving"] = srv
+        print(f"bench: serving done in {rep.makespan:.2f} s", file=sys.stderr, flush=True)
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.uint8, device=dev)  # 256 MiB
         b = torch.empty_like(a)
@@ -222,6 +280,7 @@ def main():
         extras["copy_calibration_bytes"] = a.numel()
     out["extras"] = extras
     if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, inp)
     print(json.dumps(out), flush=True)
 

@@ -127,6 +127,30 @@ void dg_destroy_mesh(dg_mesh* mesh);
  *   u, r: device vectors of dg_num_dofs(mesh, 0) entries; u != r. */
 int dg_apply_velocity_residual(const dg_mesh* mesh, dg_prec prec, const void* u, void* r, void* stream);
 
+/* Most meshes one batched call takes. */
+#define DG_MAX_BATCH 4096
+
+/* Device workspace (bytes) of a batched velocity call over n meshes, or
+ * DG_ERR_ARG when n is outside [1, DG_MAX_BATCH]. */
+int64_t dg_batch_workspace_bytes(int32_t n);
+
+/* The velocity residual of paper Sec. 4.2 (as dg_apply_velocity_residual)
+ * for n independent meshes in as few launches as there are distinct
+ * (degree, quadrature, curved) groups: the cells of every mesh of a group
+ * are concatenated into one grid.  Entry i writes r[i] = R_i(u[i]) on
+ * meshes[i]; the result is bit-for-bit that of the single-mesh call.  This is
+ * the serving path for many small wall-modelled channels (one per request).
+ *   meshes, u, r: host arrays of n entries; u[i], r[i] device vectors as for
+ *                 the single-mesh call; outputs must be pairwise distinct.
+ *   workspace:    device, 256-byte aligned, >= dg_batch_workspace_bytes(n);
+ *                 it holds the launch descriptors, so it must not be reused
+ *                 before the launches on `stream` have run.
+ *   The call stages the descriptors with a copy and waits for `stream` to
+ *   reach it (work queued earlier on `stream` is waited for too).
+ *   Errors: DG_ERR_ARG, DG_ERR_WORKSPACE, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
+int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, dg_prec prec, const void* const* u,
+                                       void* const* r, void* workspace, size_t ws_bytes, void* stream);
+
 /* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
  * term, flux eq. ipflux) with homogeneous Neumann data on the walls:
  *   (A p)(q) = sum_e (grad q, grad p)_e + sum_{interior F} [ -1/2 (grad q.n)(p- - p+)
@@ -160,6 +184,10 @@ typedef struct {
 
 /* Bytes of device workspace dg_solve_poisson needs. */
 int64_t dg_solve_workspace_bytes(const dg_mesh* mesh, const dg_solve_params* sp);
+
+/* The same size computed from mesh parameters before any mesh exists (for
+ * admission by device-memory footprint); DG_ERR_ARG on invalid parameters. */
+int64_t dg_solve_workspace_bytes_for(const dg_mesh_params* params, const dg_solve_params* sp);
 
 /* Solve A x = b for the singular SIP Poisson operator (null space: constants;
  * the pressure equation of the paper's dual-splitting step, Sec. 4.1-4.2).

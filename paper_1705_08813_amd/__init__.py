@@ -14,7 +14,8 @@ import ctypes
 from . import _lib
 from ._lib import DG_F32, DG_F64, DgError, SolveParams, SolveStats
 
-__all__ = ["Mesh", "DgError", "DG_F64", "DG_F32", "SolveParams", "SolveStats"]
+__all__ = ["Mesh", "DgError", "DG_F64", "DG_F32", "SolveParams", "SolveStats", "apply_velocity_residual_batched",
+           "batch_workspace"]
 
 
 def _stream_ptr(stream):
@@ -136,3 +137,38 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+
+def batch_workspace(n, device=None):
+    """Device workspace for a batched velocity call over n meshes."""
+    import torch
+    nbytes = _lib.check(_lib.lib().dg_batch_workspace_bytes(int(n)))
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+
+
+def apply_velocity_residual_batched(meshes, us, rs=None, workspace=None, stream=None):
+    """r_i = R_i(u_i) for every mesh of the list in one batched call
+    (bit-for-bit the single-mesh result).  All vectors share one dtype."""
+    import torch
+    n = len(meshes)
+    if n == 0 or len(us) != n or (rs is not None and len(rs) != n):
+        raise ValueError("meshes, us and rs must be non-empty lists of one length")
+    if rs is None:
+        rs = [torch.empty_like(u) for u in us]
+    prec = None
+    for m, u, r in zip(meshes, us, rs):
+        pu = m._check_vec(u, m.n_vel, "u")
+        if m._check_vec(r, m.n_vel, "r") != pu or (prec is not None and pu != prec):
+            raise ValueError("every u and r of a batch must have one dtype")
+        prec = pu
+    if workspace is None:
+        workspace = batch_workspace(n, meshes[0].device)
+    VP = ctypes.c_void_p
+    hs = (VP * n)(*[m.handle.value for m in meshes])
+    up = (VP * n)(*[u.data_ptr() for u in us])
+    rp = (VP * n)(*[r.data_ptr() for r in rs])
+    _lib.check(_lib.lib().dg_apply_velocity_residual_batched(hs, n, prec, up, rp, _dptr(workspace),
+                                                             workspace.numel(), _stream_ptr(stream)))
+    return rs
+

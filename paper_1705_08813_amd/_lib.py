@@ -59,9 +59,14 @@ _SIGS = {
     "dg_num_enriched": (ctypes.c_int64, [_VP]),
     "dg_destroy_mesh": (None, [_VP]),
     "dg_apply_velocity_residual": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "dg_batch_workspace_bytes": (ctypes.c_int64, [ctypes.c_int32]),
+    "dg_apply_velocity_residual_batched": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.c_int,
+                                                          ctypes.POINTER(_VP), ctypes.POINTER(_VP), _VP,
+                                                          ctypes.c_size_t, _VP]),
     "dg_apply_poisson": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "dg_poisson_diagonal": (ctypes.c_int, [_VP, _VP, _VP]),
     "dg_solve_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.POINTER(SolveParams)]),
+    "dg_solve_workspace_bytes_for": (ctypes.c_int64, [ctypes.POINTER(MeshParams), ctypes.POINTER(SolveParams)]),
     "dg_solve_poisson": (ctypes.c_int, [_VP, ctypes.POINTER(SolveParams), _VP, _VP, _VP, ctypes.c_size_t,
                                         ctypes.POINTER(SolveStats), _VP]),
     "dg_last_error": (ctypes.c_char_p, []),

@@ -129,6 +129,14 @@ int64_t dg_mesh_workspace_bytes(const dg_mesh_params* params) {
   return (int64_t)layout(m).total;
 }
 
+int64_t dg_solve_workspace_bytes_for(const dg_mesh_params* params, const dg_solve_params* sp) {
+  if (!params || !sp) return set_error(DG_ERR_ARG, "params/solve params is NULL");
+  dg_mesh m{};
+  int rc = derive(*params, m);
+  if (rc) return rc;
+  return (int64_t)solve_bytes_n(m.n_p);
+}
+
 int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* workspace, size_t ws_bytes,
                   void* stream, dg_mesh** out) {
   if (!params || !out) return set_error(DG_ERR_ARG, "params/out is NULL");
@@ -261,6 +269,27 @@ int dg_apply_velocity_residual(const dg_mesh* m, dg_prec prec, const void* u, vo
   if (u == r) return set_error(DG_ERR_ARG, "u and r must not alias");
   if (!aligned256(u) || !aligned256(r)) return set_error(DG_ERR_ARG, "u and r must be 256-byte aligned");
   return launch_velocity(m, prec, u, r, static_cast<hipStream_t>(stream));
+}
+
+int64_t dg_batch_workspace_bytes(int32_t n) {
+  if (n < 1 || n > DG_MAX_BATCH) return set_error(DG_ERR_ARG, "batch size must be in [1, DG_MAX_BATCH]");
+  return batch_workspace_bytes(n);
+}
+
+int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, dg_prec prec, const void* const* u,
+                                       void* const* r, void* workspace, size_t ws_bytes, void* stream) {
+  if (!meshes || !u || !r || !workspace) return set_error(DG_ERR_ARG, "meshes/u/r/workspace is NULL");
+  if (n < 1 || n > DG_MAX_BATCH) return set_error(DG_ERR_ARG, "batch size must be in [1, DG_MAX_BATCH]");
+  if (prec != DG_F64 && prec != DG_F32) return set_error(DG_ERR_ARG, "unknown precision");
+  if (!aligned256(workspace)) return set_error(DG_ERR_ARG, "workspace must be 256-byte aligned");
+  for (int i = 0; i < n; ++i) {
+    if (!meshes[i] || !u[i] || !r[i]) return set_error(DG_ERR_ARG, "a batch entry has a NULL mesh/u/r");
+    if (u[i] == r[i]) return set_error(DG_ERR_ARG, "u and r of a batch entry must not alias");
+    if (!aligned256(u[i]) || !aligned256(r[i])) return set_error(DG_ERR_ARG, "u and r must be 256-byte aligned");
+    for (int j = 0; j < i; ++j)
+      if (r[j] == r[i]) return set_error(DG_ERR_ARG, "two batch entries share an output vector");
+  }
+  return launch_velocity_batched(meshes, n, prec, u, r, workspace, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 int dg_apply_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, void* stream) {

@@ -111,6 +111,10 @@ int launch_geometry(const dg_mesh* m, hipStream_t s);
 int launch_poisson_diag(const dg_mesh* m, hipStream_t s);
 int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+int64_t batch_workspace_bytes(int n);
+size_t solve_bytes_n(int64_t n_p);  // device workspace of dg_solve_poisson for n_p pressure unknowns
+int launch_velocity_batched(const dg_mesh* const* meshes, int n, dg_prec prec, const void* const* u, void* const* r,
+                            void* ws, size_t ws_bytes, hipStream_t s);
 bool poisson_supported(int np, int nq);
 bool velocity_supported(int np, int nq, int nqy);
 const char* velocity_combos();

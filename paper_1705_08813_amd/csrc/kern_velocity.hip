@@ -640,9 +640,11 @@ __device__ __forceinline__ void vel_faces_dir_curved(const MeshDev& M, int64_t e
   __syncthreads();
 }
 
+// One cell: block-local index b within its launch (regular cells: layer range
+// [layer_lo, layer_lo + nlayers); enriched cells: the enriched index).
 template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
-__global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
-                                                  int layer_lo, int nlayers) {
+__device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
+                                         int layer_lo, int nlayers) {
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr TabLayout L = tab_layout(NP, NQ, NQY);
   constexpr int NP3 = Sh::NP3, NPTS = Sh::NPTS;
@@ -655,7 +657,6 @@ __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* _
   __shared__ T s_tab[FaceTab<NP, NQ, NQY>::size];
   const int tid = threadIdx.x, nt = blockDim.x;
 
-  const int b = blockIdx.x;
   const int ex = b % M.nx;
   const int t0 = b / M.nx;
   int ey, ez;
@@ -818,6 +819,43 @@ __global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* _
   }
 }
 
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
+__global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
+                                                  int layer_lo, int nlayers) {
+  vel_cell<T, NP, NQ, NQY, ENR, CURVED>(M, u, r, blockIdx.x, layer_lo, nlayers);
+}
+
+}  // namespace
+
+// One mesh of a batched launch.
+struct VelBatchItem {
+  MeshDev M;
+  const void* u;
+  void* r;
+  int layer_lo, nlayers;
+};
+
+namespace {
+
+// Cells of many meshes (same degree and rules) in one launch: block b takes
+// cell b of the concatenated cell ranges; prefix[i] is the first block of
+// item i.  Each cell runs exactly the code of the single-mesh kernel, so the
+// results are bit-for-bit the same.
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
+__global__ __launch_bounds__(256, 3) void vel_kernel_batched(const VelBatchItem* __restrict__ items,
+                                                          const int64_t* __restrict__ prefix, int nitems) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = nitems;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const VelBatchItem& it = items[lo];
+  vel_cell<T, NP, NQ, NQY, ENR, CURVED>(it.M, static_cast<const T*>(it.u), static_cast<T*>(it.r),
+                                        (int)(b - prefix[lo]), it.layer_lo, it.nlayers);
+}
+
 template <typename T, int NP, int NQ, int NQW>
 int launch_vel_t(const dg_mesh* m, const MeshDev& M, const void* u, void* r, hipStream_t s) {
   const T* uu = static_cast<const T*>(u);
@@ -883,6 +921,25 @@ MeshDev make_meshdev_u(const dg_mesh* m) {
   X(5, 7, 8)             \
   X(6, 8, 8)
 
+// Regular-layer range of a mesh (cells not in an enriched layer).
+static void regular_layers(const dg_mesh* m, int& lo, int& nl) {
+  lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  nl = hi - lo + 1;
+}
+
+template <typename T, int NP, int NQ, int NQW, bool CURVED>
+static void launch_batch_group(const VelBatchItem* d_items_reg, const int64_t* d_pre_reg, int nreg, int64_t tot_reg,
+                               const VelBatchItem* d_items_enr, const int64_t* d_pre_enr, int nenr, int64_t tot_enr,
+                               hipStream_t s) {
+  if (nreg > 0 && tot_reg > 0)
+    hipLaunchKernelGGL((vel_kernel_batched<T, NP, NQ, NQ, false, CURVED>), dim3((unsigned)tot_reg), dim3(256), 0, s,
+                       d_items_reg, d_pre_reg, nreg);
+  if (nenr > 0 && tot_enr > 0)
+    hipLaunchKernelGGL((vel_kernel_batched<T, NP, NQ, NQW, true, CURVED>), dim3((unsigned)tot_enr), dim3(256), 0, s,
+                       d_items_enr, d_pre_enr, nenr);
+}
+
 bool velocity_supported(int np, int nq, int nqy) {
 #define X(a, b, c) \
   if (np == a && nq == b && nqy == c) return true;
@@ -905,6 +962,111 @@ int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipS
   DG_VEL_COMBOS(X)
 #undef X
   return set_error(DG_ERR_UNSUPPORTED, "velocity degree/quadrature combination not compiled");
+}
+
+}  // namespace dgwm
+
+namespace dgwm {
+
+// At most two descriptors per mesh (regular and enriched cells) and, per
+// group and class, one prefix entry per descriptor plus the total.
+int64_t batch_workspace_bytes(int n) {
+  const size_t items = ((2 * (size_t)n * sizeof(VelBatchItem)) + 255) & ~size_t(255);
+  return (int64_t)(items + (4 * (size_t)n + 2) * sizeof(int64_t));
+}
+
+// Groups the meshes by compiled combination and launches one batched kernel
+// per group and cell class (regular / enriched).
+int launch_velocity_batched(const dg_mesh* const* meshes, int n, dg_prec prec, const void* const* u, void* const* r,
+                            void* ws, size_t ws_bytes, hipStream_t s) {
+  if ((int64_t)ws_bytes < batch_workspace_bytes(n)) return set_error(DG_ERR_WORKSPACE, "batch workspace too small");
+  struct Key {
+    int np, nq, nqw, curved;
+    bool operator==(const Key& o) const { return np == o.np && nq == o.nq && nqw == o.nqw && curved == o.curved; }
+  };
+  std::vector<Key> keys;
+  std::vector<int> key_of(n);
+  for (int i = 0; i < n; ++i) {
+    const dg_mesh* m = meshes[i];
+    Key k{m->np_u, m->P.nq_u, m->nenr > 0 ? m->P.nq_wn : -1, m->curved};
+    int j = 0;
+    for (; j < (int)keys.size(); ++j)
+      if (keys[j] == k) break;
+    if (j == (int)keys.size()) keys.push_back(k);
+    key_of[i] = j;
+  }
+  // host staging: per group, regular items then enriched items, with prefixes
+  std::vector<VelBatchItem> items;
+  std::vector<int64_t> pre;
+  struct Group { int ireg, nreg, preg, ienr, nenr, penr; int64_t treg, tenr; Key k; };
+  std::vector<Group> groups;
+  for (int g = 0; g < (int)keys.size(); ++g) {
+    Group G{};
+    G.k = keys[g];
+    for (int cls = 0; cls < 2; ++cls) {
+      const int first = (int)items.size(), pfirst = (int)pre.size();
+      int64_t tot = 0;
+      for (int i = 0; i < n; ++i) {
+        if (key_of[i] != g) continue;
+        const dg_mesh* m = meshes[i];
+        int lo, nl;
+        regular_layers(m, lo, nl);
+        const int64_t nb = cls == 0 ? (nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0) : m->nenr;
+        if (nb == 0) continue;
+        VelBatchItem it{};
+        it.M = make_meshdev_u(m);
+        it.u = u[i];
+        it.r = r[i];
+        it.layer_lo = lo;
+        it.nlayers = nl;
+        items.push_back(it);
+        pre.push_back(tot);
+        tot += nb;
+      }
+      pre.push_back(tot);
+      if (cls == 0) { G.ireg = first; G.nreg = (int)items.size() - first; G.preg = pfirst; G.treg = tot; }
+      else { G.ienr = first; G.nenr = (int)items.size() - first; G.penr = pfirst; G.tenr = tot; }
+    }
+    groups.push_back(G);
+  }
+  char* base = static_cast<char*>(ws);
+  VelBatchItem* d_items = reinterpret_cast<VelBatchItem*>(base);
+  int64_t* d_pre = reinterpret_cast<int64_t*>(base + ((items.size() * sizeof(VelBatchItem) + 255) & ~size_t(255)));
+  int rc = DG_OK;
+  if (!items.empty())
+    rc = check_hip(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(VelBatchItem), hipMemcpyHostToDevice, s),
+                   "batch items");
+  if (!rc) rc = check_hip(hipMemcpyAsync(d_pre, pre.data(), pre.size() * sizeof(int64_t), hipMemcpyHostToDevice, s),
+                          "batch prefixes");
+  // the staging vectors are released on return: wait for the copies
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "batch staging");
+  if (rc) return rc;
+  for (const Group& G : groups) {
+    bool done = false;
+#define X(a, b, c)                                                                                               \
+  if (!done && G.k.np == a && G.k.nq == b && (G.k.nqw == c || G.k.nqw < 0)) {                                    \
+    done = true;                                                                                                 \
+    if (prec == DG_F64) {                                                                                        \
+      if (G.k.curved)                                                                                            \
+        launch_batch_group<double, a, b, c, true>(d_items + G.ireg, d_pre + G.preg, G.nreg, G.treg,              \
+                                                  d_items + G.ienr, d_pre + G.penr, G.nenr, G.tenr, s);          \
+      else                                                                                                       \
+        launch_batch_group<double, a, b, c, false>(d_items + G.ireg, d_pre + G.preg, G.nreg, G.treg,             \
+                                                   d_items + G.ienr, d_pre + G.penr, G.nenr, G.tenr, s);         \
+    } else {                                                                                                     \
+      if (G.k.curved)                                                                                            \
+        launch_batch_group<float, a, b, c, true>(d_items + G.ireg, d_pre + G.preg, G.nreg, G.treg,               \
+                                                 d_items + G.ienr, d_pre + G.penr, G.nenr, G.tenr, s);           \
+      else                                                                                                       \
+        launch_batch_group<float, a, b, c, false>(d_items + G.ireg, d_pre + G.preg, G.nreg, G.treg,              \
+                                                  d_items + G.ienr, d_pre + G.penr, G.nenr, G.tenr, s);          \
+    }                                                                                                            \
+  }
+    DG_VEL_COMBOS(X)
+#undef X
+    if (!done) return set_error(DG_ERR_UNSUPPORTED, "velocity combination not compiled");
+  }
+  return check_hip(hipGetLastError(), "batched velocity launch");
 }
 
 }  // namespace dgwm

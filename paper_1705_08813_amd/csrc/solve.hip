@@ -281,13 +281,17 @@ namespace {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t solve_bytes(const dg_mesh* m) {
-  const size_t n = (size_t)m->n_p;
+size_t solve_bytes(const dg_mesh* m) { return dgwm::solve_bytes_n(m->n_p); }
+
+}  // namespace
+
+namespace dgwm {
+size_t solve_bytes_n(int64_t n_p) {
+  const size_t n = (size_t)n_p;
   return 9 * up256(n * sizeof(double)) + 9 * up256(n * sizeof(float)) + up256(64 * sizeof(double)) +
          up256(kRedBlocks * sizeof(double));
 }
-
-}  // namespace
+}  // namespace dgwm
 
 extern "C" {
 

@@ -142,3 +142,52 @@ def draw_inputs(wl: Workload, want=("u", "tau", "p"), dtype=np.float64):
 
 def random_vector(n: int, seed: int, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
+# ---------------------------------------------------------------- serving ---
+
+@dataclass(frozen=True)
+class ServingConfig:
+    """A seeded stream of channel-instance requests (Poisson arrivals)."""
+
+    n_requests: int = 512
+    mean_interarrival: float = 0.005          # seconds (200 requests/s)
+    seed: int = 5
+    grids: tuple = ((8, 8, 8), (16, 8, 8), (16, 16, 16), (32, 16, 16))
+    degrees: tuple = (2, 3, 4, 5)
+    viscosities: tuple = (1.0 / 180.0, 1.0 / 395.0, 1.0 / 590.0)
+    gamma: float = 1.8
+    tau_lo: float = 0.5
+    tau_hi: float = 1.5
+    applies: int = 10                         # velocity-residual applies per request
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+@dataclass(frozen=True)
+class Request:
+    rid: int
+    arrival: float                            # seconds after the stream starts
+    workload: Workload
+
+
+def serving_requests(cfg: ServingConfig):
+    """Arrival times (exponential gaps), then per request the grid, degree
+    and viscosity drawn uniformly from the listed sets.  Pressure degree is
+    k - 1 with k_p + 1 Gauss points; velocity uses floor(3k/2)+1 points."""
+    rng = np.random.default_rng(cfg.seed)
+    gaps = rng.exponential(cfg.mean_interarrival, size=cfg.n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    gi = rng.integers(0, len(cfg.grids), size=cfg.n_requests)
+    ki = rng.integers(0, len(cfg.degrees), size=cfg.n_requests)
+    vi = rng.integers(0, len(cfg.viscosities), size=cfg.n_requests)
+    out = []
+    for i in range(cfg.n_requests):
+        nx, ny, nz = cfg.grids[gi[i]]
+        k = int(cfg.degrees[ki[i]])
+        mesh = MeshConfig(nx=nx, ny=ny, nz=nz, gamma=cfg.gamma, k_u=k, k_p=k - 1, nq_u=default_nq_u(k),
+                          nq_p=k, nq_wn=8, nu=float(cfg.viscosities[vi[i]]))
+        wl = Workload(f"request{i}", mesh, seed=cfg.seed * 1_000_003 + i, tau_lo=cfg.tau_lo, tau_hi=cfg.tau_hi)
+        out.append(Request(i, float(arrivals[i]), wl))
+    return out
