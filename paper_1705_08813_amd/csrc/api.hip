@@ -93,7 +93,8 @@ WsLayout layout(const dg_mesh& m) {
   L.hy = o; o = up256(o + sizeof(double) * m.P.ny);
   L.tab_u = o;
   o = up256(o + sizeof(double) * (tab_layout(m.np_u, m.P.nq_u, m.P.nq_wn).size + m.P.nq_u + m.P.nq_wn));
-  L.tab_p = o; o = up256(o + sizeof(double) * tab_layout(m.np_p, m.P.nq_p, m.P.nq_p).size);
+  L.tab_p = o;
+  o = up256(o + sizeof(double) * (tab_layout(m.np_p, m.P.nq_p, m.P.nq_p).size + poi_ops(m.np_p).size));
   L.tau = o; o = up256(o + sizeof(double) * m.n_tau);
   L.psi = o; o = up256(o + sizeof(double) * 4 * (size_t)m.nenr * m.psi_pts);
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
@@ -187,11 +188,12 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   }
   for (int j = 0; j < P.ny; ++j) hy[j] = eta[j + 1] - eta[j];
   const TabLayout Lu = tab_layout(m->np_u, P.nq_u, P.nq_wn);
-  std::vector<double> tu(Lu.size + P.nq_u + P.nq_wn), tp(tab_layout(m->np_p, P.nq_p, P.nq_p).size);
+  std::vector<double> tu(Lu.size + P.nq_u + P.nq_wn), tp(tab_layout(m->np_p, P.nq_p, P.nq_p).size + poi_ops(m->np_p).size);
   fill_tables(m->np_u, P.nq_u, P.nq_wn, tu.data());
   for (int q = 0; q < P.nq_u; ++q) tu[Lu.size + q] = tu[Lu.g + q];
   for (int q = 0; q < P.nq_wn; ++q) tu[Lu.size + P.nq_u + q] = tu[Lu.gy + q];
   fill_tables(m->np_p, P.nq_p, P.nq_p, tp.data());
+  fill_poisson_ops(m->np_p, P.nq_p, tp.data() + tab_layout(m->np_p, P.nq_p, P.nq_p).size);
   std::vector<double> tau(m->n_tau, 1.0);
   if (tau_w_host) {
     for (int64_t i = 0; i < m->n_tau; ++i) {

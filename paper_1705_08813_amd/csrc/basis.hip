@@ -141,4 +141,29 @@ void fill_tables(int np, int nq, int nqy, double* out) {
   for (int i = 0; i < np; ++i) out[L.gl + i] = gl[i];
 }
 
+void fill_poisson_ops(int np, int nq, double* out) {
+  const PoiOps o = poi_ops(np);
+  double gl[kMaxP], g[kMaxQ], w[kMaxQ], v[kMaxQ][kMaxP], d[kMaxQ][kMaxP];
+  lobatto_nodes(np, gl);
+  gauss_rule(nq, g, w);
+  for (int q = 0; q < nq; ++q) lagrange_eval(gl, np, g[q], v[q], d[q]);
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) {
+      double m = 0, k = 0;
+      for (int q = 0; q < nq; ++q) {
+        m += w[q] * v[q][i] * v[q][j];
+        k += w[q] * d[q][i] * d[q][j];
+      }
+      out[o.M + i * np + j] = m;
+      out[o.K + i * np + j] = k;
+    }
+  double v0[kMaxP], d0[kMaxP];
+  lagrange_eval(gl, np, 0.0, v0, d0);
+  for (int i = 0; i < np; ++i) out[o.nd0 + i] = d0[i];
+  lagrange_eval(gl, np, 1.0, v0, d0);
+  for (int i = 0; i < np; ++i) out[o.nd1 + i] = d0[i];
+  float* f = reinterpret_cast<float*>(out + o.f32);
+  for (int i = 0; i < o.n; ++i) f[i] = (float)out[i];
+}
+
 }  // namespace dgwm

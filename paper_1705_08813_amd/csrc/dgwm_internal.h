@@ -49,6 +49,27 @@ __host__ __device__ constexpr TabLayout tab_layout(int np, int nq, int nqy) {
   return t;
 }
 
+// 1-D operator tables of the Poisson kernel, stored after the pressure
+// tab_layout block: reference mass M_ij = sum_q w_q N_i(g_q) N_j(g_q) and
+// stiffness K_ij = sum_q w_q N_i'(g_q) N_j'(g_q) with the Gauss rule of the
+// operator, N_i'(0), N_i'(1); first in double, then the same entries in float.
+struct PoiOps {
+  int M, K, nd0, nd1, n;  // offsets inside one precision block; n entries per block
+  int f32;                // offset (in doubles) of the float block
+  int size;               // doubles in total
+};
+__host__ __device__ constexpr PoiOps poi_ops(int np) {
+  PoiOps o{};
+  o.M = 0;
+  o.K = np * np;
+  o.nd0 = 2 * np * np;
+  o.nd1 = 2 * np * np + np;
+  o.n = 2 * np * np + 2 * np;
+  o.f32 = o.n;
+  o.size = o.n + (o.n + 1) / 2;
+  return o;
+}
+
 // Points of the enrichment tables of one enriched cell: the volume rule
 // nq x nqy x nq, then the six faces f = 2d + s in order.  Face (d,s) has
 // tangential directions t1 < t2; its points are q1 + Q1 q2 with Q = nqy for
@@ -65,6 +86,7 @@ __host__ __device__ constexpr int psi_points(int nq, int nqy) { return psi_face_
 
 // Host-side 1-D tables (basis.cpp).
 void fill_tables(int np, int nq, int nqy, double* out);
+void fill_poisson_ops(int np, int nq, double* out);  // poi_ops(np).size doubles
 void gauss_rule(int n, double* x, double* w);
 void lobatto_nodes(int n, double* x);
 

@@ -28,6 +28,7 @@ struct MeshDev {
   int geo_stride;
   const double* tauF; // [cell][face]
   int nq_wn;          // wall-normal points of enriched cells (the point layout of their tables)
+  int ops_off;        // offset of the Poisson operator tables (poi_ops) inside tab
 };
 
 // Enriched index of cell (ex, ey, ez) or -1.

@@ -13,242 +13,247 @@ namespace dgwm {
 
 namespace {
 
-template <typename T, int NP, int NQ>
-struct PoiShape {
-  static constexpr int NP2 = NP * NP, NP3 = NP * NP * NP, NPTS = NQ * NQ * NQ, FP = NQ * NQ;
-  static constexpr int NL = 6 * 2 * NP2;   // neighbour layers [face][val|d_n][NP2]
-  static constexpr int OL = 6 * 2 * NP2;   // own layers
-  static constexpr int FL = 6 * 2 * FP;    // fluxes [face][q-test | d_n q-test][pt]
-  static constexpr int RB = 6 * 2 * NP2;   // integrated face tests [face][value | normal][NP2]
-  static constexpr int FACE = NL + OL + FL + RB;
-  static constexpr int VOL = 4 * NPTS;
-  static constexpr int BIG = VOL > FACE ? VOL : FACE;
-};
-
-// node index base + l * stride of the line along direction D through (a, b)
-template <int NP>
-__device__ __forceinline__ void poi_line(int D, int a, int b, int& base, int& stride) {
-  if (D == 0) {
-    base = NP * (a + NP * b);
-    stride = 1;
-  } else if (D == 1) {
-    base = a + NP * NP * b;
-    stride = NP;
-  } else {
-    base = a + NP * b;
-    stride = NP * NP;
-  }
-}
-
-// neighbour across face (D, S): -1 for a (Neumann) wall
+// Neighbour of cell (ex, ey, ez) across face (D, S): -1 for a (Neumann)
+// wall.  ny1 receives the neighbour's layer index.
 __device__ __forceinline__ int64_t poi_nb(const MeshDev& M, int ex, int ey, int ez, int D, int S, int& ny1) {
-  int n[3] = {ex, ey, ez};
+  int x = ex, yy = ey, z = ez;
+  int& j = D == 0 ? x : (D == 1 ? yy : z);
   const int nmax = D == 0 ? M.nx : (D == 1 ? M.ny : M.nz);
-  int j = n[D] + (S ? 1 : -1);
+  j += S ? 1 : -1;
   if (j < 0 || j >= nmax) {
     if (D == 1 && !M.fully_periodic) return -1;
     j = (j + nmax) % nmax;
   }
-  n[D] = j;
-  ny1 = n[1];
-  return n[0] + (int64_t)M.nx * (n[1] + (int64_t)M.ny * n[2]);
+  ny1 = yy;
+  return x + (int64_t)M.nx * (yy + (int64_t)M.ny * z);
 }
 
-template <typename T, int NP, int NQ>
-__global__ __launch_bounds__(64) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y) {
-  using Sh = PoiShape<T, NP, NQ>;
-  constexpr TabLayout L = tab_layout(NP, NQ, NQ);
-  constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3, NPTS = Sh::NPTS, FP = Sh::FP;
-  __shared__ T s_p[NP3];
-  __shared__ T s_r[NP3];
-  __shared__ T s_nl[Sh::NL];
-  __shared__ T s_big[Sh::BIG];
-  __shared__ T s_ft[NQ * NP + NQ + 2 * NP];  // S, w, N'(0), N'(1) for the face phases
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t e = blockIdx.x;
-  const int ex = (int)(e % M.nx), ey = (int)((e / M.nx) % M.ny), ez = (int)(e / ((int64_t)M.nx * M.ny));
-  const T hx = T(M.hx), hz = T(M.hz), hy = T(M.hy[ey]);
-  auto hdir = [&](int d) { return d == 0 ? hx : (d == 1 ? hy : hz); };
-  const double* Sq = M.tab + L.S;  // volume sweeps: uniform indices, scalar cache
-  const double* Dq = M.tab + L.D;
-  const double* wq = M.tab + L.w;
-  const double* nd0 = M.tab + L.nd0;
-  const double* nd1 = M.tab + L.nd1;
+// Cells per workgroup: one thread per pencil (line of NP nodes), so a cell
+// uses NP^2 threads and a 256-thread workgroup holds 256 / NP^2 cells.
+template <int NP>
+struct PoiBlk {
+  static constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
+  static constexpr int CB = 256 / NP2 > 0 ? 256 / NP2 : 1;
+  static constexpr int NT = CB * NP2;
+};
 
-  // own values, face tables, and the six neighbour face layers (value, normal derivative)
-  for (int i = tid; i < NP3; i += nt) s_p[i] = p[e * NP3 + i];
-  for (int i = tid; i < NQ * NP + NQ + 2 * NP; i += nt) {
-    const int o = i < NQ * NP ? L.S + i : (i < NQ * NP + NQ ? L.w + i - NQ * NP : L.nd0 + i - NQ * NP - NQ);
-    s_ft[i] = T(M.tab[o]);
-  }
-  for (int t = tid; t < 6 * NP2; t += nt) {
-    const int f = t / NP2, k = t - f * NP2;
-    const int D = f >> 1, S = f & 1;
-    int ny1 = 0;
-    const int64_t nb = poi_nb(M, ex, ey, ez, D, S, ny1);
-    T val = 0, der = 0;
-    if (nb >= 0) {
-      int base, stride;
-      poi_line<NP>(D, k % NP, k / NP, base, stride);
-      const T* src = p + nb * NP3 + base;
-      const double* nd = S ? nd0 : nd1;  // neighbour's face is at xi_D = 1 - S
-      T x[NP];
-#pragma unroll
-      for (int l = 0; l < NP; ++l) x[l] = src[l * stride];
-#pragma unroll
-      for (int l = 0; l < NP; ++l) der += T(nd[l]) * x[l];
-      val = x[S ? 0 : NP - 1];
-      const T hdn = D == 1 ? T(M.hy[ny1]) : hdir(D);
-      der /= hdn;
-    }
-    s_nl[(f * 2 + 0) * NP2 + k] = val;
-    s_nl[(f * 2 + 1) * NP2 + k] = der;
-  }
-  __syncthreads();
+// Pencil through tangential node (a, b) along direction D: first node and stride.
+template <int NP>
+__device__ __forceinline__ int pencil_base(int D, int a, int b) {
+  return D == 0 ? NP * (a + NP * b) : (D == 1 ? a + NP * NP * b : a + NP * b);
+}
+template <int NP>
+__device__ __forceinline__ constexpr int pencil_stride(int D) {
+  return D == 0 ? 1 : (D == 1 ? NP : NP * NP);
+}
 
-  // volume term: (grad q, grad p) by sum factorization
-  T* s_val = s_big;
-  T* s_grad = s_big + NPTS;  // [d][pt]
-  {
-    T* tA = s_grad;
-    T* tB = tA + NQ * NP * NP;
-    sweep<0, NP, NP, NP, NQ, false, false>(s_p, NP3, tA, 0, Sq, T(1), 1);
-    __syncthreads();
-    sweep<1, NQ, NP, NP, NQ, false, false>(tA, 0, tB, 0, Sq, T(1), 1);
-    __syncthreads();
-    sweep<2, NQ, NQ, NP, NQ, false, false>(tB, 0, s_val, 0, Sq, T(1), 1);
-    __syncthreads();
-  }
-  const T vol = hx * hy * hz;
-  sweep<0, NQ, NQ, NQ, NQ, false, false>(s_val, 0, s_grad + 0 * NPTS, 0, Dq, T(1) / hx, 1);
-  sweep<1, NQ, NQ, NQ, NQ, false, false>(s_val, 0, s_grad + 1 * NPTS, 0, Dq, T(1) / hy, 1);
-  sweep<2, NQ, NQ, NQ, NQ, false, false>(s_val, 0, s_grad + 2 * NPTS, 0, Dq, T(1) / hz, 1);
-  __syncthreads();
-  for (int pt = tid; pt < NPTS; pt += nt) {
-    const int qx = pt % NQ, qy = (pt / NQ) % NQ, qz = pt / (NQ * NQ);
-    const T w = T(wq[qx]) * T(wq[qy]) * T(wq[qz]) * vol;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) s_grad[d * NPTS + pt] *= w;
-  }
-  __syncthreads();
-  sweep<0, NQ, NQ, NQ, NQ, true, false>(s_grad + 0 * NPTS, 0, s_val, 0, Dq, T(1) / hx, 1);
-  __syncthreads();
-  sweep<1, NQ, NQ, NQ, NQ, true, true>(s_grad + 1 * NPTS, 0, s_val, 0, Dq, T(1) / hy, 1);
-  __syncthreads();
-  sweep<2, NQ, NQ, NQ, NQ, true, true>(s_grad + 2 * NPTS, 0, s_val, 0, Dq, T(1) / hz, 1);
-  __syncthreads();
-  {
-    T* tB = s_grad;
-    T* tA = tB + NQ * NQ * NP;
-    sweep<2, NQ, NQ, NQ, NP, true, false>(s_val, 0, tB, 0, Sq, T(1), 1);
-    __syncthreads();
-    sweep<1, NQ, NQ, NP, NP, true, false>(tB, 0, tA, 0, Sq, T(1), 1);
-    __syncthreads();
-    sweep<0, NQ, NP, NP, NP, true, false>(tA, 0, s_r, 0, Sq, T(1), 1);
-    __syncthreads();
-  }
+// Poisson operator on box cells.  On an affine box cell every term
+// separates: with the reference mass M and stiffness K of the 1-D basis
+// (built with the operator's Gauss rule, hence identical to quadrature),
+//   cell:   (hy hz/hx) Mz My Kx + (hx hz/hy) Mz Ky Mx + (hx hy/hz) Kz My Mx
+//   face D: (area) M_t1 M_t2 applied to a face source s_D that lives on the
+//           pencils along D: for the face at xi_D = s with outward sign sg,
+//           jump J = p- - p+ and G = tau J - sg {{dp/dx_D}},
+//           s_D(l) += -1/2 sg N_l'(s)/h_D J + [l is the face node] G.
+// Writing Q_D = (area_D/h_D) K_D p + area_D s_D (pencil-local along D),
+//   A p = Mx (My Qz + Mz Qy) + My Mz Qx,
+// evaluated as z-, y-, x-sweeps over LDS.  Each thread owns one pencil of
+// every direction of its cell and reads the six neighbour pencils it needs
+// for the traces straight from global memory (no atomics: every output has
+// one writer).
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y,
+                                                      int64_t ncell, int nblocks) {
+  using BL = PoiBlk<NP>;
+  constexpr int NP2 = BL::NP2, NP3 = BL::NP3, CB = BL::CB;
+  __shared__ T s_P[CB * NP3];
+  __shared__ T s_X[CB * NP3];
+  __shared__ T s_Y[CB * NP3];
+  __shared__ T s_Z[CB * NP3];
 
-  // face terms of all six faces (tables from LDS: their indices vary across lanes)
-  const T* fS = s_ft;
-  const T* fw = s_ft + NQ * NP;
-  const T* fnd0 = fw + NQ;
-  const T* fnd1 = fnd0 + NP;
-  T* ol = s_big;              // own layers [face][val|d_n][NP2]
-  T* fl = ol + Sh::OL;        // fluxes [face][2][FP]
-  T* rb = fl + Sh::FL;        // [face][value test | normal test][NP2]
-  for (int t = tid; t < 6 * NP2; t += nt) {
-    const int f = t / NP2, k = t - f * NP2;
-    const int D = f >> 1, S = f & 1;
-    int base, stride;
-    poi_line<NP>(D, k % NP, k / NP, base, stride);
-    const T* nd = S ? fnd1 : fnd0;
-    T der = 0;
+  // contiguous cell ranges per XCD (workgroups are dealt round-robin over 8)
+  const int bid = blockIdx.x;
+  const int q8 = nblocks >> 3, r8 = nblocks & 7, xcd = bid & 7, m8 = bid >> 3;
+  const int blk = xcd * q8 + (xcd < r8 ? xcd : r8) + m8;
+
+  const int tid = threadIdx.x;
+  const int c = tid / NP2, t = tid - c * NP2;
+  const int a = t % NP, b = t / NP;
+  const int64_t e = (int64_t)blk * CB + c;
+  const bool live = tid < BL::NT && e < ncell;
+
+  constexpr PoiOps O = poi_ops(NP);
+  const T* ops = sizeof(T) == 8 ? reinterpret_cast<const T*>(M.tab + M.ops_off)
+                                : reinterpret_cast<const T*>(M.tab + M.ops_off + O.f32);
+  const T* Mm = ops + O.M;
+  const T* Km = ops + O.K;
+  const T* nd0 = ops + O.nd0;
+  const T* nd1 = ops + O.nd1;
+
+  T* sP = s_P + c * NP3;
+  T* sX = s_X + c * NP3;
+  T* sY = s_Y + c * NP3;
+  T* sZ = s_Z + c * NP3;
+
+  T px[NP];
+  T vnb[3][2], dnb[3][2], hnb[3][2];
+  bool wall[3][2];
+  T h[3];
+  if (live) {
+    const int ex = (int)(e % M.nx), ey = (int)((e / M.nx) % M.ny), ez = (int)(e / ((int64_t)M.nx * M.ny));
+    h[0] = T(M.hx);
+    h[1] = T(M.hy[ey]);
+    h[2] = T(M.hz);
+    const T* pe = p + e * NP3;
+    const int bx = pencil_base<NP>(0, a, b);
 #pragma unroll
-    for (int l = 0; l < NP; ++l) der += T(nd[l]) * s_p[base + l * stride];
-    ol[(f * 2 + 0) * NP2 + k] = s_p[base + (S ? NP - 1 : 0) * stride];
-    ol[(f * 2 + 1) * NP2 + k] = der / hdir(D);
-  }
-  __syncthreads();
-  // traces of both sides at the face Gauss points, then the SIP flux
-  for (int t = tid; t < 6 * FP; t += nt) {
-    const int f = t / FP, pt = t - f * FP;
-    const int D = f >> 1, S = f & 1;
-    int ny1 = 0;
-    if (poi_nb(M, ex, ey, ez, D, S, ny1) < 0) {
-      fl[(f * 2 + 0) * FP + pt] = 0;
-      fl[(f * 2 + 1) * FP + pt] = 0;
-      continue;
-    }
-    const int q1 = pt % NQ, q2 = pt / NQ;
-    const T* lo = ol + f * 2 * NP2;
-    const T* ln = s_nl + f * 2 * NP2;
-    T vm = 0, dm = 0, vp = 0, dp = 0;
+    for (int l = 0; l < NP; ++l) px[l] = pe[bx + l];
 #pragma unroll
-    for (int i2 = 0; i2 < NP; ++i2) {
-      T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-      for (int i1 = 0; i1 < NP; ++i1) {
-        const T s1 = (fS[q1 * NP + i1]);
-        a0 += s1 * lo[i1 + NP * i2];
-        a1 += s1 * lo[NP2 + i1 + NP * i2];
-        a2 += s1 * ln[i1 + NP * i2];
-        a3 += s1 * ln[NP2 + i1 + NP * i2];
-      }
-      const T s2 = (fS[q2 * NP + i2]);
-      vm += s2 * a0;
-      dm += s2 * a1;
-      vp += s2 * a2;
-      dp += s2 * a3;
-    }
-    const int T1 = D == 0 ? 1 : 0, T2 = D == 2 ? 1 : 2;
-    const T ht1 = hdir(T1), ht2 = hdir(T2), hd = hdir(D);
-    const T hdn = D == 1 ? T(M.hy[ny1]) : hd;
-    const T tauF = T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
-    const T sg = S ? T(1) : T(-1);
-    const T wf = (fw[q1]) * (fw[q2]) * ht1 * ht2;
-    const T jmp = vm - vp;
-    const T avg_n = T(0.5) * (dm + dp) * sg;
-    fl[(f * 2 + 0) * FP + pt] = wf * (-avg_n + tauF * jmp);      // tested with q
-    fl[(f * 2 + 1) * FP + pt] = wf * (T(-0.5) * jmp * sg);       // tested with d q / d x_D
-  }
-  __syncthreads();
-  // integrate against the face traces of the test functions
-  for (int t = tid; t < 6 * NP2; t += nt) {
-    const int f = t / NP2, k = t - f * NP2;
-    const int i1 = k % NP, i2 = k / NP;
-    const T* a = fl + f * 2 * FP;
-    T rv = 0, bn = 0;
-#pragma unroll
-    for (int q2 = 0; q2 < NQ; ++q2) {
-      T a0 = 0, a1 = 0;
-#pragma unroll
-      for (int q1 = 0; q1 < NQ; ++q1) {
-        const T s1 = (fS[q1 * NP + i1]);
-        a0 += s1 * a[q1 + NQ * q2];
-        a1 += s1 * a[FP + q1 + NQ * q2];
-      }
-      rv += (fS[q2 * NP + i2]) * a0;
-      bn += (fS[q2 * NP + i2]) * a1;
-    }
-    rb[(f * 2 + 0) * NP2 + k] = rv;
-    rb[(f * 2 + 1) * NP2 + k] = bn / hdir(f >> 1);
-  }
-  __syncthreads();
-  // scatter: every node gathers the contributions of the six faces
-  for (int B = tid; B < NP3; B += nt) {
-    const int ii[3] = {B % NP, (B / NP) % NP, B / NP2};
-    T acc = s_r[B];
+    for (int l = 0; l < NP; ++l) sP[bx + l] = px[l];
+    // traces of the six neighbours on the shared faces: value and d/dx_D
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
-      const int a = D == 0 ? ii[1] : ii[0];
-      const int b = D == 2 ? ii[1] : ii[2];
-      const int k = a + NP * b;
-      const int l = ii[D];
-      acc += (fnd0[l]) * rb[((2 * D + 0) * 2 + 1) * NP2 + k] + (fnd1[l]) * rb[((2 * D + 1) * 2 + 1) * NP2 + k];
-      if (l == 0) acc += rb[((2 * D + 0) * 2 + 0) * NP2 + k];
-      if (l == NP - 1) acc += rb[((2 * D + 1) * 2 + 0) * NP2 + k];
+      const int bD = pencil_base<NP>(D, a, b);
+#pragma unroll
+      for (int S = 0; S < 2; ++S) {
+        int ny1 = ey;
+        const int64_t nb = poi_nb(M, ex, ey, ez, D, S, ny1);
+        wall[D][S] = nb < 0;
+        T v = 0, d = 0, hn = h[D];
+        if (nb >= 0) {
+          const T* pn = p + nb * NP3 + bD;
+          T q[NP];
+#pragma unroll
+          for (int l = 0; l < NP; ++l) q[l] = pn[l * pencil_stride<NP>(D)];
+          // neighbour below (S = 0) meets us at its xi_D = 1, above (S = 1) at xi_D = 0
+          const T* nd = S ? nd0 : nd1;
+#pragma unroll
+          for (int l = 0; l < NP; ++l) d += nd[l] * q[l];
+          v = S ? q[0] : q[NP - 1];
+          if (D == 1) hn = T(M.hy[ny1]);
+          d /= hn;
+        }
+        vnb[D][S] = v;
+        dnb[D][S] = d;
+        hnb[D][S] = hn;
+      }
     }
-    y[e * NP3 + B] = acc;
+  }
+  __syncthreads();
+
+  // Q_D on the thread's pencil of every direction
+  if (live) {
+    const T pen = T(M.pen);
+#pragma unroll
+    for (int D = 0; D < 3; ++D) {
+      const int bD = pencil_base<NP>(D, a, b);
+      T x[NP];
+      if (D == 0) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) x[l] = px[l];
+      } else {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) x[l] = sP[bD + l * pencil_stride<NP>(D)];
+      }
+      const T hd = h[D];
+      const T area = D == 0 ? h[1] * h[2] : (D == 1 ? h[0] * h[2] : h[0] * h[1]);
+      T d0 = 0, d1 = 0;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        d0 += nd0[l] * x[l];
+        d1 += nd1[l] * x[l];
+      }
+      d0 /= hd;
+      d1 /= hd;
+      T J0 = 0, G0 = 0, J1 = 0, G1 = 0;
+      if (!wall[D][0]) {  // face at xi_D = 0, outward sign -1
+        const T tau = pen * (T(1) / hd > T(1) / hnb[D][0] ? T(1) / hd : T(1) / hnb[D][0]);
+        J0 = x[0] - vnb[D][0];
+        G0 = tau * J0 + T(0.5) * (d0 + dnb[D][0]);
+      }
+      if (!wall[D][1]) {  // face at xi_D = 1, outward sign +1
+        const T tau = pen * (T(1) / hd > T(1) / hnb[D][1] ? T(1) / hd : T(1) / hnb[D][1]);
+        J1 = x[NP - 1] - vnb[D][1];
+        G1 = tau * J1 - T(0.5) * (d1 + dnb[D][1]);
+      }
+      const T cv = area / hd;
+      T* dst = D == 0 ? sX : (D == 1 ? sY : sZ);
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        T k = 0;
+#pragma unroll
+        for (int m = 0; m < NP; ++m) k += Km[l * NP + m] * x[m];
+        T q = cv * (k + T(0.5) * nd0[l] * J0 - T(0.5) * nd1[l] * J1);
+        if (l == 0) q += area * G0;
+        if (l == NP - 1) q += area * G1;
+        dst[bD + l * pencil_stride<NP>(D)] = q;
+      }
+    }
+  }
+  __syncthreads();
+
+  // z sweeps: Y <- Mz Qy, X <- Mz Qx
+  if (live) {
+    const int bz = pencil_base<NP>(2, a, b);
+    constexpr int sz = NP * NP;
+    T u[NP], w[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      u[l] = sY[bz + l * sz];
+      w[l] = sX[bz + l * sz];
+    }
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      T su = 0, sw = 0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        su += Mm[l * NP + m] * u[m];
+        sw += Mm[l * NP + m] * w[m];
+      }
+      sY[bz + l * sz] = su;
+      sX[bz + l * sz] = sw;
+    }
+  }
+  __syncthreads();
+
+  // y sweeps: Z <- My Qz + Y, X <- My X
+  if (live) {
+    const int by = pencil_base<NP>(1, a, b);
+    T u[NP], w[NP], v[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      u[l] = sZ[by + l * NP];
+      v[l] = sY[by + l * NP];
+      w[l] = sX[by + l * NP];
+    }
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      T su = v[l], sw = 0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        su += Mm[l * NP + m] * u[m];
+        sw += Mm[l * NP + m] * w[m];
+      }
+      sZ[by + l * NP] = su;
+      sX[by + l * NP] = sw;
+    }
+  }
+  __syncthreads();
+
+  // x sweep and write-out: y = Mx Z + X
+  if (live) {
+    const int bx = pencil_base<NP>(0, a, b);
+    T u[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) u[l] = sZ[bx + l];
+    T* ye = y + e * NP3 + bx;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      T s = sX[bx + l];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) s += Mm[l * NP + m] * u[m];
+      ye[l] = s;
+    }
   }
 }
 
@@ -331,6 +336,7 @@ MeshDev make_meshdev_p(const dg_mesh* m) {
   M.hz = m->hz;
   M.hy = m->hy;
   M.tab = m->tab_p;
+  M.ops_off = tab_layout(m->np_p, m->P.nq_p, m->P.nq_p).size;
   M.pen = m->P.ip_factor_p * (m->P.k_p + 1.0) * (m->P.k_p + 1.0);
   return M;
 }
@@ -351,15 +357,15 @@ const char* poisson_combos() { return "poisson (k+1, nq_p): (2,2) (3,3) (4,4) (5
 
 int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s) {
   const MeshDev M = make_meshdev_p(m);
-  const unsigned nb = (unsigned)m->ncell;
 #define X(a, b)                                                                                           \
   if (m->np_p == a && m->P.nq_p == b) {                                                                   \
+    const int nb = (int)((m->ncell + PoiBlk<a>::CB - 1) / PoiBlk<a>::CB);                                 \
     if (prec == DG_F64)                                                                                   \
-      hipLaunchKernelGGL((poisson_kernel<double, a, b>), dim3(nb), dim3(64), 0, s, M,                     \
-                         static_cast<const double*>(p), static_cast<double*>(y));                         \
+      hipLaunchKernelGGL((poisson_kernel<double, a>), dim3(nb), dim3(256), 0, s, M,                       \
+                         static_cast<const double*>(p), static_cast<double*>(y), m->ncell, nb);           \
     else                                                                                                  \
-      hipLaunchKernelGGL((poisson_kernel<float, a, b>), dim3(nb), dim3(64), 0, s, M,                      \
-                         static_cast<const float*>(p), static_cast<float*>(y));                           \
+      hipLaunchKernelGGL((poisson_kernel<float, a>), dim3(nb), dim3(256), 0, s, M,                        \
+                         static_cast<const float*>(p), static_cast<float*>(y), m->ncell, nb);             \
     return check_hip(hipGetLastError(), "poisson kernel launch");                                         \
   }
   DG_POI_COMBOS(X)
