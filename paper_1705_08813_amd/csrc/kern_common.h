@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "ctab.h"
 #include "dgwm_internal.h"
 
 namespace dgwm {
@@ -85,6 +86,54 @@ __device__ __forceinline__ void sweep(const T* __restrict__ in, int IS, T* __res
       T s = 0;
 #pragma unroll
       for (int n = 0; n < NI; ++n) s += T(TR ? mat[n * MO + m] : mat[m * NI + n]) * v[n];
+      if (ADD)
+        dst[m * SOUT] += scale * s;
+      else
+        dst[m * SOUT] = scale * s;
+    }
+  }
+}
+
+// As sweep, with a compile-time matrix MAT::at(row, col) (MO x NI, or NI x MO
+// with TR): every entry is a literal of the unrolled code.
+// The workgroup size NT is a compile-time constant, so a line count below NT
+// gives each thread at most one line and the table literals stay local to
+// straight-line code.
+template <int DIR, int I0, int I1, int I2, int MO, bool TR, bool ADD, typename MAT, int NT = 256, typename T>
+__device__ __forceinline__ void sweep_c(const T* __restrict__ in, int IS, T* __restrict__ out, int OS, T scale,
+                                        int ncomp) {
+  constexpr int NI = DIR == 0 ? I0 : (DIR == 1 ? I1 : I2);
+  constexpr int O0 = DIR == 0 ? MO : I0;
+  constexpr int O1 = DIR == 1 ? MO : I1;
+  constexpr int P0 = DIR == 0 ? I1 : I0;
+  constexpr int P1 = DIR == 2 ? I1 : I2;
+  constexpr int NPEN = P0 * P1;
+  constexpr int SIN = DIR == 0 ? 1 : (DIR == 1 ? I0 : I0 * I1);
+  constexpr int SOUT = DIR == 0 ? 1 : (DIR == 1 ? O0 : O0 * O1);
+  for (int t = threadIdx.x; t < NPEN * ncomp; t += NT) {
+    const int c = t / NPEN, p = t - c * NPEN;
+    const int a = p % P0, b = p / P0;
+    int ib, ob;
+    if (DIR == 0) {
+      ib = I0 * (a + I1 * b);
+      ob = O0 * (a + O1 * b);
+    } else if (DIR == 1) {
+      ib = a + I0 * I1 * b;
+      ob = a + O0 * O1 * b;
+    } else {
+      ib = a + I0 * b;
+      ob = a + O0 * b;
+    }
+    const T* src = in + c * IS + ib;
+    T* dst = out + c * OS + ob;
+    T v[NI];
+#pragma unroll
+    for (int n = 0; n < NI; ++n) v[n] = src[n * SIN];
+#pragma unroll
+    for (int m = 0; m < MO; ++m) {
+      T s = 0;
+#pragma unroll
+      for (int n = 0; n < NI; ++n) s += T(TR ? MAT::at(n, m) : MAT::at(m, n)) * v[n];
       if (ADD)
         dst[m * SOUT] += scale * s;
       else

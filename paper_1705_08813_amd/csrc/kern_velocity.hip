@@ -29,7 +29,9 @@ struct VelShape {
   static constexpr int A1 = 2 * 2 * 7 * Q1MAX * NP;     // t1-swept traces [s][side][field][q1][i2]
   static constexpr int FL = 2 * 8 * FMAX;               // fluxes [s][field][pt]
   static constexpr int B1 = 2 * 3 * 3 * Q1MAX * NP;     // t2-transposed tests [s][c][3][q1][i2]
-  static constexpr int FACE = NL + LAYO + A1 + FL + B1;
+  static constexpr int TRC = 2 * 2 * 8 * FMAX;          // traces [s][side][field][pt]
+  static constexpr int FACE0 = NL + LAYO + A1 + TRC;
+  static constexpr int FACE = FACE0 > NL + LAYO + A1 + FL + B1 ? FACE0 : NL + LAYO + A1 + FL + B1;
   // curved cells: 12 trace fields per side and reference-gradient tests
   static constexpr int A1C = 2 * 2 * 3 * 3 * Q1MAX * NP;
   static constexpr int FLC = 2 * 12 * FMAX;
@@ -87,7 +89,7 @@ __device__ __forceinline__ void load_neighbour_layers(const MeshDev& M, const T*
                                                       const double* tab_nd0, const double* tab_nd1, int ex, int ey,
                                                       int ez, bool need_nut) {
   constexpr int NP2 = NP * NP, NP3 = NP * NP * NP;
-  for (int t = threadIdx.x; t < 6 * 3 * NP2; t += blockDim.x) {
+  for (int t = threadIdx.x; t < 6 * 3 * NP2; t += 256) {
     const int f = t / (3 * NP2), rem = t - f * 3 * NP2;
     const int c = rem / NP2, k = rem - c * NP2;
     const int D = f >> 1, S = f & 1;
@@ -155,12 +157,15 @@ __device__ __forceinline__ void load_face_tab(const double* tab, T* s_tab) {
 // u_c, d_D u_c (c = 0..2), and the tangential derivatives d_T1 u_D, d_T2 u_D
 // ({{2 nu eps(u)}} n needs (grad u + grad u^T) e_D), and the adjoint term
 // -theta nu sym(j (x) n) tests only d_D phi_c and d_T phi_D.
+//
+// Every 1-D contraction runs as a thread-owned line with the table entries
+// as literals of the unrolled code (one LDS read per input, none per
+// coefficient); phases are separated by workgroup barriers.
 template <typename T, int NP, int NQ, int NQY, bool ENR, int D>
 __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, const T* s_nl, const T* s_nut, T* s_r,
-                                              T* s_face, const T* s_ut, const T* s_tab, int ex, int ey, int ez,
-                                              int64_t enr, T hx, T hy, T hz, T rt[3]) {
+                                              T* s_face, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
+                                              T hy, T hz, T rt[3]) {
   using Sh = VelShape<T, NP, NQ, NQY>;
-  constexpr TabLayout L = tab_layout(NP, NQ, NQY);
   constexpr int T1 = D == 0 ? 1 : 0;
   constexpr int T2 = D == 2 ? 1 : 2;
   constexpr int Q1 = T1 == 1 ? NQY : NQ;
@@ -168,58 +173,60 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   constexpr int FP = Q1 * Q2;
   constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3;
   constexpr int QN = Q1 * NP;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  using TL = FaceTab<NP, NQ, NQY>;
-  const T* S1 = s_tab + (T1 == 1 ? TL::Sy : TL::Sq);
-  const T* Sd1 = s_tab + (T1 == 1 ? TL::Sdy : TL::Sdq);
-  const T* w1 = s_tab + (T1 == 1 ? TL::wy : TL::wq);
-  const T* S2 = s_tab + (T2 == 1 ? TL::Sy : TL::Sq);
-  const T* Sd2 = s_tab + (T2 == 1 ? TL::Sdy : TL::Sdq);
-  const T* w2 = s_tab + (T2 == 1 ? TL::wy : TL::wq);
-  const T* nd0 = s_tab + TL::nd0;
-  const T* nd1 = s_tab + TL::nd1;
-  (void)L;
+  constexpr auto& tb1 = ct::tab<NP, Q1>;
+  constexpr auto& tb2 = ct::tab<NP, Q2>;
+  constexpr auto& tbn = ct::tab<NP, NQ>;  // nd0, nd1 do not depend on the rule
+  const int tid = threadIdx.x;
+  constexpr int nt = 256;  // workgroup size of every velocity launch
 
-  T* lay = s_face;                 // [s][c][val|d_n][NP2]
-  T* A1 = lay + Sh::LAYO;          // [s][side][field 0..6][q1][i2]
-  T* fl = A1 + Sh::A1;             // [s][field 0..7][pt]
-  T* B1 = fl + Sh::FL;             // [s][c][value|t1|normal][q1][i2]
+  // LDS regions (see VelShape::FACE): X = own layers, later fluxes and line
+  // results; Y = t1-swept traces; Z = traces, later t2-transposed tests
+  T* lay = s_face;                     // [s][c][val|d_n][NP2]
+  T* A1 = lay + Sh::LAYO;              // [s][side][field 0..6][q1][i2]
+  T* TR = A1 + Sh::A1;                 // [s][side][field 0..7][pt]
+  T* FL = s_face;                      // [s][field 0..7][pt]
+  T* B1 = TR;                          // [s][test 0..6][q1][i2]
+  T* RB = s_face;                      // [s][c][value|normal][NP2]
 
   const T hown[3] = {hx, hy, hz};
   const T hd = hown[D], ht1 = hown[T1], ht2 = hown[T2];
-  // neighbours of the two faces (scalars, selected by s without local arrays)
+  const T ihd = T(1) / hd, iht1 = T(1) / ht1, iht2 = T(1) / ht2;
   const FaceNb nb0 = face_nb(M, ex, ey, ez, D, 0), nb1 = face_nb(M, ex, ey, ez, D, 1);
   auto tau_of = [&](const FaceNb& nb) {
-    const T hdn = (D == 1) ? T(M.hy[nb.nidx1]) : hd;
-    return nb.wall ? T(M.pen * M.wall_mult) / hd : T(M.pen) * (T(1) / hd > T(1) / hdn ? T(1) / hd : T(1) / hdn);
+    const T ihn = (D == 1) ? T(1) / T(M.hy[nb.nidx1]) : ihd;
+    return nb.wall ? T(M.pen * M.wall_mult) * ihd : T(M.pen) * (ihd > ihn ? ihd : ihn);
   };
   const T tau0 = tau_of(nb0), tau1 = tau_of(nb1);
   const bool wall0 = nb0.wall, wall1 = nb1.wall;
   const int64_t enrn0 = nb0.enr_nb, enrn1 = nb1.enr_nb;
 
-  // Phase A: own node layers of both faces
-  for (int t = tid; t < 2 * 3 * NP2; t += nt) {
-    const int s = t / (3 * NP2), rem = t - s * 3 * NP2;
-    const int c = rem / NP2, k = rem - c * NP2;
+  // Phase A: own node layers of both faces (value, d/dx_D), one line each
+  for (int t = tid; t < 3 * NP2; t += nt) {
+    const int c = t / NP2, k = t - c * NP2;
     int base, stride;
     line_of<NP>(D, k % NP, k / NP, base, stride);
-    const T* nd = s ? nd1 : nd0;
     const T* src = s_u + c * NP3 + base;
-    T der = 0;
+    T x[NP];
 #pragma unroll
-    for (int l = 0; l < NP; ++l) der += T(nd[l]) * src[l * stride];
-    lay[((s * 3 + c) * 2 + 0) * NP2 + k] = src[(s ? NP - 1 : 0) * stride];
-    lay[((s * 3 + c) * 2 + 1) * NP2 + k] = der / hd;
+    for (int l = 0; l < NP; ++l) x[l] = src[l * stride];
+    T d0 = 0, d1 = 0;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      d0 += T(tbn.nd0[l]) * x[l];
+      d1 += T(tbn.nd1[l]) * x[l];
+    }
+    lay[((0 * 3 + c) * 2 + 0) * NP2 + k] = x[0];
+    lay[((0 * 3 + c) * 2 + 1) * NP2 + k] = d0 * ihd;
+    lay[((1 * 3 + c) * 2 + 0) * NP2 + k] = x[NP - 1];
+    lay[((1 * 3 + c) * 2 + 1) * NP2 + k] = d1 * ihd;
   }
   __syncthreads();
 
-  // Phase B1: sweep along t1 (node i1 -> Gauss q1).  Fields: 0-2 value of
+  // Phase B1: lines along t1 (node i1 -> Gauss q1).  Fields: 0-2 value of
   // u_c, 3-5 normal derivative of u_c, 6 t1-derivative of u_D.
-  for (int t = tid; t < 2 * 2 * 7 * QN; t += nt) {
-    const int q1 = t % Q1;
-    int r = t / Q1;
-    const int i2 = r % NP;
-    r /= NP;
+  for (int t = tid; t < 2 * 2 * 7 * NP; t += nt) {
+    const int i2 = t % NP;
+    int r = t / NP;
     const int f = r % 7;
     r /= 7;
     const int side = r % 2, s = r / 2;
@@ -228,15 +235,66 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     const int fld = (f >= 3 && f < 6) ? 1 : 0;
     const T* lv = (side == 0 ? lay + ((s * 3 + c) * 2) * NP2 : s_nl + (((2 * D + s) * 3 + c) * 2) * NP2) +
                   fld * NP2 + NP * i2;
-    const T* mat = (f == 6 ? Sd1 : S1) + q1 * NP;
-    T acc = 0;
+    T x[NP];
 #pragma unroll
-    for (int i1 = 0; i1 < NP; ++i1) acc += T(mat[i1]) * lv[i1];
-    A1[(((s * 2 + side) * 7 + f) * Q1 + q1) * NP + i2] = acc;
+    for (int i1 = 0; i1 < NP; ++i1) x[i1] = lv[i1];
+    T* o = A1 + (((s * 2 + side) * 7 + f) * Q1) * NP + i2;
+    if (f == 6) {
+#pragma unroll
+      for (int q1 = 0; q1 < Q1; ++q1) {
+        T acc = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < NP; ++i1) acc += T(tb1.Sd[q1][i1]) * x[i1];
+        o[q1 * NP] = acc * iht1;
+      }
+    } else {
+#pragma unroll
+      for (int q1 = 0; q1 < Q1; ++q1) {
+        T acc = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < NP; ++i1) acc += T(tb1.S[q1][i1]) * x[i1];
+        o[q1 * NP] = acc;
+      }
+    }
   }
   __syncthreads();
 
-  // Phase C: traces at each face point (sweep along t2), then the flux
+  // Phase C1: lines along t2 (node i2 -> Gauss q2), giving the 8 trace
+  // fields of each side; field 7 = d_T2 u_D from the value of u_D.
+  for (int t = tid; t < 2 * 2 * 8 * Q1; t += nt) {
+    const int q1 = t % Q1;
+    int r = t / Q1;
+    const int fo = r % 8;
+    r /= 8;
+    const int side = r % 2, s = r / 2;
+    if (side == 1 && (s ? wall1 : wall0)) continue;
+    const int fin = fo < 7 ? fo : D;
+    const T* a = A1 + (((s * 2 + side) * 7 + fin) * Q1 + q1) * NP;
+    T x[NP];
+#pragma unroll
+    for (int i2 = 0; i2 < NP; ++i2) x[i2] = a[i2];
+    T* o = TR + ((s * 2 + side) * 8 + fo) * FP + q1;
+    if (fo == 7) {
+#pragma unroll
+      for (int q2 = 0; q2 < Q2; ++q2) {
+        T acc = 0;
+#pragma unroll
+        for (int i2 = 0; i2 < NP; ++i2) acc += T(tb2.Sd[q2][i2]) * x[i2];
+        o[q2 * Q1] = acc * iht2;
+      }
+    } else {
+#pragma unroll
+      for (int q2 = 0; q2 < Q2; ++q2) {
+        T acc = 0;
+#pragma unroll
+        for (int i2 = 0; i2 < NP; ++i2) acc += T(tb2.S[q2][i2]) * x[i2];
+        o[q2 * Q1] = acc;
+      }
+    }
+  }
+  __syncthreads();
+
+  // Phase C2: numerical flux at each face point
   const T nu = T(M.nu), theta = T(M.theta);
   for (int t = tid; t < 2 * FP; t += nt) {
     const int s = t / FP, pt = t - s * FP;
@@ -247,21 +305,10 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     // tr[side][0..2] u_c, [3..5] d_D u_c, [6] d_T1 u_D, [7] d_T2 u_D
     T tr[2][8];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      if (side == 1 && wall) continue;
-      const T* a = A1 + ((s * 2 + side) * 7) * QN + q1 * NP;
+    for (int f = 0; f < 8; ++f) tr[0][f] = TR[((s * 2 + 0) * 8 + f) * FP + pt];
+    if (!wall) {
 #pragma unroll
-      for (int f = 0; f < 7; ++f) {
-        T v = 0;
-#pragma unroll
-        for (int i2 = 0; i2 < NP; ++i2) v += T(S2[q2 * NP + i2]) * a[f * QN + i2];
-        tr[side][f] = v;
-      }
-      T d2 = 0;
-#pragma unroll
-      for (int i2 = 0; i2 < NP; ++i2) d2 += T(Sd2[q2 * NP + i2]) * a[D * QN + i2];
-      tr[side][6] /= ht1;
-      tr[side][7] = d2 / ht2;
+      for (int f = 0; f < 8; ++f) tr[1][f] = TR[((s * 2 + 1) * 8 + f) * FP + pt];
     }
     T psim = 0, gpsim[3] = {0, 0, 0};
     if (ENR) {
@@ -298,12 +345,12 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     const T unm = sg * tr[0][D], unp = sg * tr[1][D];
     const T am = unm < 0 ? -unm : unm, ap = unp < 0 ? -unp : unp;
     const T lam = T(2) * (am > ap ? am : ap);
-    const T wf = T(w1[q1]) * T(w2[q2]) * ht1 * ht2;
+    const T wf = T(tb1.w[q1]) * T(tb2.w[q2]) * ht1 * ht2;
     const T tau = s ? tau1 : tau0;
     T jmp[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) jmp[c] = tr[0][c] - tr[1][c];
-    T* fo = fl + s * 8 * FP + pt;
+    T* fo = FL + s * 8 * FP + pt;
     const T hth = T(0.5) * theta * nu * sg;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -331,64 +378,97 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   }
   __syncthreads();
 
-  // Phase D1: transposed sweep along t2 (q2 -> i2):
-  //   value test a0 = S2^T fv_c (+ Sd2^T F[D][T2]/ht2 for c = D),
-  //   t1-derivative test a1 = S2^T F[D][T1] (c = D only),
-  //   normal-derivative test a3 = S2^T F[c][D]
-  for (int t = tid; t < 2 * 3 * QN; t += nt) {
-    const int i2 = t % NP;
-    int r = t / NP;
-    const int q1 = r % Q1;
-    r /= Q1;
-    const int c = r % 3, s = r / 3;
-    const T* fo = fl + s * 8 * FP + q1;
-    T a0 = 0, a1 = 0, a3 = 0;
+  // Phase D1: lines along t2 transposed (q2 -> i2).  Tests 0-2: value test
+  // S2^T fv_c (+ Sd2^T F[D][T2] / ht2 for c = D); 3: t1-derivative test
+  // S2^T F[D][T1]; 4-6: normal-derivative test S2^T F[c][D].
+  for (int t = tid; t < 2 * 7 * Q1; t += nt) {
+    const int q1 = t % Q1;
+    int r = t / Q1;
+    const int o = r % 7, s = r / 7;
+    const int fin = o < 3 ? o : (o == 3 ? 6 : o - 1);
+    const T* a = FL + (s * 8 + fin) * FP + q1;
+    T x[Q2];
 #pragma unroll
-    for (int q2 = 0; q2 < Q2; ++q2) {
-      const T b2 = T(S2[q2 * NP + i2]);
-      a0 += b2 * fo[c * FP + Q1 * q2];
-      a3 += b2 * fo[(3 + c) * FP + Q1 * q2];
-      if (c == D) {
-        a0 += T(Sd2[q2 * NP + i2]) / ht2 * fo[7 * FP + Q1 * q2];
-        a1 += b2 * fo[6 * FP + Q1 * q2];
+    for (int q2 = 0; q2 < Q2; ++q2) x[q2] = a[q2 * Q1];
+    T out[NP];
+#pragma unroll
+    for (int i2 = 0; i2 < NP; ++i2) {
+      T acc = 0;
+#pragma unroll
+      for (int q2 = 0; q2 < Q2; ++q2) acc += T(tb2.S[q2][i2]) * x[q2];
+      out[i2] = acc;
+    }
+    if (o == D) {
+      const T* b = FL + (s * 8 + 7) * FP + q1;
+#pragma unroll
+      for (int q2 = 0; q2 < Q2; ++q2) x[q2] = b[q2 * Q1];
+#pragma unroll
+      for (int i2 = 0; i2 < NP; ++i2) {
+        T acc = 0;
+#pragma unroll
+        for (int q2 = 0; q2 < Q2; ++q2) acc += T(tb2.Sd[q2][i2]) * x[q2];
+        out[i2] += acc * iht2;
       }
     }
-    T* o = B1 + ((s * 3 + c) * 3) * QN + q1 * NP + i2;
-    o[0] = a0;
-    o[QN] = a1;
-    o[2 * QN] = a3;
+    T* dst = B1 + ((s * 7 + o) * Q1 + q1) * NP;
+#pragma unroll
+    for (int i2 = 0; i2 < NP; ++i2) dst[i2] = out[i2];
   }
   __syncthreads();
 
-  // Phase D2: transposed sweep along t1 (q1 -> i1) and scatter onto the line
-  // of nodes along D (value test on the face layer, normal-derivative test on
-  // every layer); one thread per line, both faces, so no write conflicts.
+  // Phase D2: lines along t1 transposed (q1 -> i1): value test of u_c on the
+  // face layer, and the normal-derivative test (to be spread along D).
+  for (int t = tid; t < 2 * 3 * 2 * NP; t += nt) {
+    const int i2 = t % NP;
+    int r = t / NP;
+    const int kind = r % 2;
+    r /= 2;
+    const int c = r % 3, s = r / 3;
+    const T* a = B1 + ((s * 7 + (kind ? 4 + c : c)) * Q1) * NP + i2;
+    T x[Q1];
+#pragma unroll
+    for (int q1 = 0; q1 < Q1; ++q1) x[q1] = a[q1 * NP];
+    T out[NP];
+#pragma unroll
+    for (int i1 = 0; i1 < NP; ++i1) {
+      T acc = 0;
+#pragma unroll
+      for (int q1 = 0; q1 < Q1; ++q1) acc += T(tb1.S[q1][i1]) * x[q1];
+      out[i1] = acc;
+    }
+    if (kind == 0 && c == D) {
+      const T* b = B1 + ((s * 7 + 3) * Q1) * NP + i2;
+#pragma unroll
+      for (int q1 = 0; q1 < Q1; ++q1) x[q1] = b[q1 * NP];
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) {
+        T acc = 0;
+#pragma unroll
+        for (int q1 = 0; q1 < Q1; ++q1) acc += T(tb1.Sd[q1][i1]) * x[q1];
+        out[i1] += acc * iht1;
+      }
+    }
+    const T sc = kind ? ihd : T(1);
+    T* dst = RB + ((s * 3 + c) * 2 + kind) * NP2 + NP * i2;
+#pragma unroll
+    for (int i1 = 0; i1 < NP; ++i1) dst[i1] = out[i1] * sc;
+  }
+  __syncthreads();
+
+  // Phase E: spread onto the lines of nodes along D (value test on the face
+  // layer, normal-derivative test on every layer); one thread per line.
   for (int t = tid; t < 3 * NP2; t += nt) {
     const int c = t / NP2, k = t - c * NP2;
-    const int i1 = k % NP, i2 = k / NP;
-    T rv[2], bn[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const T* b = B1 + ((s * 3 + c) * 3) * QN + i2;
-      T v = 0, n = 0;
-#pragma unroll
-      for (int q1 = 0; q1 < Q1; ++q1) {
-        const T a = T(S1[q1 * NP + i1]);
-        v += a * b[q1 * NP];
-        if (c == D) v += T(Sd1[q1 * NP + i1]) / ht1 * b[QN + q1 * NP];
-        n += a * b[2 * QN + q1 * NP];
-      }
-      rv[s] = v;
-      bn[s] = n / hd;
-    }
+    const T rv0 = RB[((0 * 3 + c) * 2 + 0) * NP2 + k], bn0 = RB[((0 * 3 + c) * 2 + 1) * NP2 + k];
+    const T rv1 = RB[((1 * 3 + c) * 2 + 0) * NP2 + k], bn1 = RB[((1 * 3 + c) * 2 + 1) * NP2 + k];
     int base, stride;
-    line_of<NP>(D, i1, i2, base, stride);
+    line_of<NP>(D, k % NP, k / NP, base, stride);
     T* dst = s_r + c * NP3 + base;
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
-      T add = T(nd0[l]) * bn[0] + T(nd1[l]) * bn[1];
-      if (l == 0) add += rv[0];
-      if (l == NP - 1) add += rv[1];
+      T add = T(tbn.nd0[l]) * bn0 + T(tbn.nd1[l]) * bn1;
+      if (l == 0) add += rv0;
+      if (l == NP - 1) add += rv1;
       dst[l * stride] += add;
     }
   }
@@ -411,7 +491,8 @@ __device__ __forceinline__ void vel_faces_dir_curved(const MeshDev& M, int64_t e
   constexpr int FP = Q1 * Q2;
   constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3;
   constexpr int QN = Q1 * NP;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nt = 256;  // workgroup size of every velocity launch
   using TL = FaceTab<NP, NQ, NQY>;
   const T* S1 = s_tab + (T1 == 1 ? TL::Sy : TL::Sq);
   const T* Sd1 = s_tab + (T1 == 1 ? TL::Sdy : TL::Sdq);
@@ -655,7 +736,8 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   __shared__ T s_nut[18];
   __shared__ T s_red[3 * 4];
   __shared__ T s_tab[FaceTab<NP, NQ, NQY>::size];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
+  constexpr int nt = 256;  // workgroup size of every velocity launch
 
   const int ex = b % M.nx;
   const int t0 = b / M.nx;
@@ -676,18 +758,18 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   const T ix = CURVED ? T(1) : T(1) / hx, iy = CURVED ? T(1) : T(1) / hy, iz = CURVED ? T(1) : T(1) / hz;
 
   const double* tab = M.tab;
-  // volume sweep matrices: uniform compile-time indices, read through the
-  // scalar cache
-  const double* Sx = tab + L.S;
-  const double* Dx = tab + L.D;
-  const double* wx = tab + L.w;
-  const double* Sy = ENR ? tab + L.Sy : tab + L.S;
-  const double* Dy = ENR ? tab + L.Dy : tab + L.D;
-  const double* wy = ENR ? tab + L.wy : tab + L.w;
+  // volume sweep matrices: compile-time tables (x and z use the NQ rule, y
+  // the NQY rule, which is NQ outside the enriched layer)
+  using Sx = ct::MatS<NP, NQ>;
+  using Sy = ct::MatS<NP, NQY>;
+  using Dx = ct::MatD<NP, NQ>;
+  using Dy = ct::MatD<NP, NQY>;
+  constexpr auto& tbx = ct::tab<NP, NQ>;
+  constexpr auto& tby = ct::tab<NP, NQY>;
 
   for (int i = tid; i < 3 * NP3; i += nt) s_u[i] = u[e * 3 * NP3 + i];
   if (ENR && tid < 3) s_ut[tid] = u[M.enr_off + enr * 3 + tid];
-  load_face_tab<T, NP, NQ, NQY, ENR>(tab, s_tab);
+  if (CURVED) load_face_tab<T, NP, NQ, NQY, ENR>(tab, s_tab);
   __syncthreads();
 
   T* s_val = s_big;             // [c][pt]
@@ -696,17 +778,17 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   {
     T* tA = s_grad;                       // (NQ, NP, NP) x 3
     T* tB = tA + 3 * NQ * NP * NP;        // (NQ, NQY, NP) x 3
-    sweep<0, NP, NP, NP, NQ, false, false>(s_u, NP3, tA, NQ * NP * NP, Sx, T(1), 3);
+    sweep_c<0, NP, NP, NP, NQ, false, false, Sx>(s_u, NP3, tA, NQ * NP * NP, T(1), 3);
     __syncthreads();
-    sweep<1, NQ, NP, NP, NQY, false, false>(tA, NQ * NP * NP, tB, NQ * NQY * NP, Sy, T(1), 3);
+    sweep_c<1, NQ, NP, NP, NQY, false, false, Sy>(tA, NQ * NP * NP, tB, NQ * NQY * NP, T(1), 3);
     __syncthreads();
-    sweep<2, NQ, NQY, NP, NQ, false, false>(tB, NQ * NQY * NP, s_val, NPTS, Sx, T(1), 3);
+    sweep_c<2, NQ, NQY, NP, NQ, false, false, Sx>(tB, NQ * NQY * NP, s_val, NPTS, T(1), 3);
     __syncthreads();
   }
   // gradients by collocation through the Gauss points
-  sweep<0, NQ, NQY, NQ, NQ, false, false>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, Dx, ix, 3);
-  sweep<1, NQ, NQY, NQ, NQY, false, false>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, Dy, iy, 3);
-  sweep<2, NQ, NQY, NQ, NQ, false, false>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, Dx, iz, 3);
+  sweep_c<0, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, ix, 3);
+  sweep_c<1, NQ, NQY, NQ, NQY, false, false, Dy>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, iy, 3);
+  sweep_c<2, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, iz, 3);
   __syncthreads();
 
   // pointwise flux G = 2 nu eps(u) - u (x) u, times the quadrature weight
@@ -724,7 +806,7 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
         for (int d = 0; d < 3; ++d) Ji[a][d] = T(g[3 * a + d]);
       wq = T(g[9]);
     } else {
-      wq = T(wx[qx]) * T(wy[qy]) * T(wx[qz]) * vol;
+      wq = T(tbx.w[qx]) * T(tby.w[qy]) * T(tbx.w[qz]) * vol;
     }
     T uu[3], gg[3][3];
 #pragma unroll
@@ -771,20 +853,20 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   __syncthreads();
 
   // integrate: W = sum_d D_d^T G_d / h_d, then transposed interpolation
-  sweep<0, NQ, NQY, NQ, NQ, true, false>(s_grad + 0 * NPTS, 3 * NPTS, s_val, NPTS, Dx, ix, 3);
+  sweep_c<0, NQ, NQY, NQ, NQ, true, false, Dx>(s_grad + 0 * NPTS, 3 * NPTS, s_val, NPTS, ix, 3);
   __syncthreads();
-  sweep<1, NQ, NQY, NQ, NQY, true, true>(s_grad + 1 * NPTS, 3 * NPTS, s_val, NPTS, Dy, iy, 3);
+  sweep_c<1, NQ, NQY, NQ, NQY, true, true, Dy>(s_grad + 1 * NPTS, 3 * NPTS, s_val, NPTS, iy, 3);
   __syncthreads();
-  sweep<2, NQ, NQY, NQ, NQ, true, true>(s_grad + 2 * NPTS, 3 * NPTS, s_val, NPTS, Dx, iz, 3);
+  sweep_c<2, NQ, NQY, NQ, NQ, true, true, Dx>(s_grad + 2 * NPTS, 3 * NPTS, s_val, NPTS, iz, 3);
   __syncthreads();
   {
     T* tB = s_grad;                       // (NQ, NQY, NP) x 3
     T* tA = tB + 3 * NQ * NQY * NP;       // (NQ, NP, NP) x 3
-    sweep<2, NQ, NQY, NQ, NP, true, false>(s_val, NPTS, tB, NQ * NQY * NP, Sx, T(1), 3);
+    sweep_c<2, NQ, NQY, NQ, NP, true, false, Sx>(s_val, NPTS, tB, NQ * NQY * NP, T(1), 3);
     __syncthreads();
-    sweep<1, NQ, NQY, NP, NP, true, false>(tB, NQ * NQY * NP, tA, NQ * NP * NP, Sy, T(1), 3);
+    sweep_c<1, NQ, NQY, NP, NP, true, false, Sy>(tB, NQ * NQY * NP, tA, NQ * NP * NP, T(1), 3);
     __syncthreads();
-    sweep<0, NQ, NP, NP, NP, true, false>(tA, NQ * NP * NP, s_r, NP3, Sx, T(1), 3);
+    sweep_c<0, NQ, NP, NP, NP, true, false, Sx>(tA, NQ * NP * NP, s_r, NP3, T(1), 3);
     __syncthreads();
   }
 
@@ -797,20 +879,17 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 0>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy,
-                                          hz, rt);
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 1>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy,
-                                          hz, rt);
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 2>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr, hx, hy,
-                                          hz, rt);
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
 
   for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
   if (ENR) {
