@@ -173,6 +173,9 @@ typedef struct {
   int32_t cheb_degree;  /* degree of the Jacobi-Chebyshev polynomial preconditioner (>= 1)      */
   double inner_rtol;    /* reserved (inner iterations run a fixed count, without host syncs)   */
   int32_t mixed;        /* 1: preconditioner in FP32; 0: everything FP64                        */
+  int32_t multigrid;    /* 1: the preconditioner is one geometric multigrid V-cycle whose        */
+                        /*    smoother is the degree-cheb_degree Jacobi-Chebyshev polynomial;    */
+                        /*    0: the polynomial alone (or the inner CG, see max_inner)           */
 } dg_solve_params;
 
 typedef struct {

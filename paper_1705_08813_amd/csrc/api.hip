@@ -16,7 +16,10 @@ thread_local std::string g_err;
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 struct WsLayout {
-  size_t eta, hy, tab_u, tab_p, tau, psi, diag, diag32, geo, meas, tauF, wdist, total;
+  size_t eta, hy, tab_u, tab_p, tau, psi, diag, diag32, geo, meas, tauF, wdist;
+  size_t mg_hy[kMaxLevels], mg_diag[kMaxLevels], mg_diag32[kMaxLevels];
+  size_t cinv, cinv32, cscr;  // coarsest pseudo-inverse (FP64, FP32) and its assembly scratch
+  size_t total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -69,6 +72,7 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
   m.hz = P.Lz / P.nz;
   m.curved = P.wall_amp != 0.0;
   m.geo_stride = m.curved ? psi_points(P.nq_u, std::max(P.nq_u, P.nq_wn)) : 0;
+  m.mg_nlev = m.curved ? 0 : mg_plan(P, m.mg);
   const int nqw_eff = m.nenr > 0 ? P.nq_wn : -1;
   if (m.nenr > 0 && !velocity_supported(m.np_u, P.nq_u, nqw_eff))
     return set_error(DG_ERR_UNSUPPORTED, std::string("velocity (k_u+1, nq_u, nq_wn) not compiled; have ") +
@@ -103,6 +107,16 @@ WsLayout layout(const dg_mesh& m) {
   L.meas = o; o = up256(o + sizeof(double) * (m.curved ? 7 * (size_t)m.ncell : 0));
   L.tauF = o; o = up256(o + sizeof(double) * (m.curved ? 6 * (size_t)m.ncell : 0));
   L.wdist = o; o = up256(o + sizeof(double) * (m.curved ? 2 * (size_t)(m.P.nx + 1) : 0));
+  for (int l = 1; l < m.mg_nlev; ++l) {
+    L.mg_hy[l] = o; o = up256(o + sizeof(double) * m.mg[l].ny);
+    L.mg_diag[l] = o; o = up256(o + sizeof(double) * m.mg[l].n);
+    L.mg_diag32[l] = o; o = up256(o + sizeof(float) * m.mg[l].n);
+  }
+  const int64_t nc = m.mg_nlev > 0 ? m.mg[m.mg_nlev - 1].n : 0;
+  const bool dense = m.mg_nlev > 0 && nc <= kMaxCoarseDofs;
+  L.cinv = o; o = up256(o + (dense ? sizeof(double) * nc * nc : 0));
+  L.cinv32 = o; o = up256(o + (dense ? sizeof(float) * nc * nc : 0));
+  L.cscr = o; o = up256(o + (dense ? 2 * sizeof(double) * nc * nc : 0));
   L.total = o;
   return L;
 }
@@ -135,7 +149,7 @@ int64_t dg_solve_workspace_bytes_for(const dg_mesh_params* params, const dg_solv
   dg_mesh m{};
   int rc = derive(*params, m);
   if (rc) return rc;
-  return (int64_t)solve_bytes_n(m.n_p);
+  return (int64_t)solve_bytes_mesh(m);
 }
 
 int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* workspace, size_t ws_bytes,
@@ -172,6 +186,16 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   m->psi = reinterpret_cast<double*>(base + W.psi);
   m->diag = reinterpret_cast<double*>(base + W.diag);
   m->diag32 = reinterpret_cast<float*>(base + W.diag32);
+  for (int l = 0; l < m->mg_nlev; ++l) {
+    if (l == 0) continue;
+    m->mg[l].hy = reinterpret_cast<double*>(base + W.mg_hy[l]);
+    m->mg[l].diag = reinterpret_cast<double*>(base + W.mg_diag[l]);
+    m->mg[l].diag32 = reinterpret_cast<float*>(base + W.mg_diag32[l]);
+  }
+  if (m->mg_nlev > 0 && m->mg[m->mg_nlev - 1].n <= kMaxCoarseDofs) {
+    m->coarse_inv = reinterpret_cast<double*>(base + W.cinv);
+    m->coarse_inv32 = reinterpret_cast<float*>(base + W.cinv32);
+  }
   if (m->curved) {
     m->geo = reinterpret_cast<double*>(base + W.geo);
     m->meas = reinterpret_cast<double*>(base + W.meas);
@@ -233,6 +257,12 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   }
   if (!rc) rc = launch_psi(m, s);
   if (!rc && !m->curved) rc = launch_poisson_diag(m, s);
+  if (!rc && m->mg_nlev > 0) {
+    m->mg[0].hy = m->hy;
+    m->mg[0].diag = m->diag;
+    m->mg[0].diag32 = m->diag32;
+    rc = mg_setup(m, eta, reinterpret_cast<double*>(base + W.cscr), s);
+  }
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "setup synchronize");
   if (rc) {
     delete m;

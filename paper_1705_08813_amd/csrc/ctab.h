@@ -152,6 +152,9 @@ struct Tab {
 template <int NP, int NQ>
 inline constexpr Tab<NP, NQ> tab{};
 
+template <int NP>
+inline constexpr Lobatto<NP> lobatto{};
+
 // Matrix views for the sweeps: at(m, n) is entry (m, n) of an MO x NI matrix.
 template <int NP, int NQ>
 struct MatS {  // N_i(g_q): rows q, columns i

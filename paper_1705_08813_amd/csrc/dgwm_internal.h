@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "dgwm.h"
 
@@ -92,6 +93,34 @@ void lobatto_nodes(int n, double* x);
 
 }  // namespace dgwm
 
+namespace dgwm {
+
+// One level of the geometric multigrid hierarchy of the pressure operator.
+// Level 0 is the mesh itself; level l+1 merges pairs of cells of level l
+// along every direction flagged in (cx, cy, cz).  The tanh-graded wall-normal
+// vertices of a coarse level are every second vertex of the finer one, so
+// the levels are nested and the coarse space is a subspace of the fine one.
+constexpr int kMaxLevels = 12;
+constexpr int kMaxCoarseDofs = 512;   // largest coarsest level solved with the dense inverse
+constexpr int kCoarseTarget = 128;    // coarsen while a level has more unknowns than this
+struct MgLevel {
+  int nx = 0, ny = 0, nz = 0;
+  int cx = 0, cy = 0, cz = 0;         // coarsened from level l-1 along x, y, z
+  int64_t ncell = 0, n = 0;
+  double hx = 0, hz = 0;
+  double* hy = nullptr;               // ny cell heights (device)
+  double* diag = nullptr;             // Jacobi diagonal (device, FP64 and FP32)
+  float* diag32 = nullptr;
+  double lam = 0.0;                   // cached Lanczos estimate of lmax(D^{-1} A)
+};
+
+// Levels of a box mesh: coarsen every direction that has an even cell count
+// (and keeps ny >= 2 between walls) while the level has more than
+// kCoarseTarget unknowns.
+int mg_plan(const dg_mesh_params& P, MgLevel* lv);
+
+}  // namespace dgwm
+
 // Host handle.  All device pointers point into the caller's workspace.
 struct dg_mesh {
   dg_mesh_params P;
@@ -119,6 +148,13 @@ struct dg_mesh {
   double* meas = nullptr; // [cell][volume, six face areas]
   double* tauF = nullptr; // [cell][face] interior-penalty parameters
   double* wdist = nullptr; // [2][nx+1] distances to the wall of the vertex rows iy = 1 and iy = ny-1
+  // pressure multigrid hierarchy (flat meshes): level 0 aliases hy/diag above
+  int mg_nlev = 0;
+  dgwm::MgLevel mg[dgwm::kMaxLevels];
+  // symmetric pseudo-inverse of the coarsest operator (zero-mean range), or
+  // nullptr when that level is larger than kMaxCoarseDofs
+  double* coarse_inv = nullptr;
+  float* coarse_inv32 = nullptr;
 };
 
 namespace dgwm {
@@ -132,9 +168,22 @@ int launch_psi(const dg_mesh* m, hipStream_t s);
 int launch_geometry(const dg_mesh* m, hipStream_t s);
 int launch_poisson_diag(const dg_mesh* m, hipStream_t s);
 int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s);
+// nvec vectors stored vstride entries apart are processed by one launch
+int launch_poisson_level(const dg_mesh* m, int level, dg_prec prec, const void* p, void* y, hipStream_t s,
+                         int nvec = 1, int64_t vstride = 0);
+int launch_poisson_diag_level(const dg_mesh* m, int level, hipStream_t s);
+// multigrid transfers between level l (fine) and l + 1 (coarse)
+int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s);
+int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, void* xf, hipStream_t s);
+// x = B b with the dense coarsest-level inverse B (n x n)
+int launch_dense_apply(int64_t n, dg_prec prec, const void* B, const void* b, void* x, hipStream_t s);
+// device workspace of dg_solve_poisson on mesh m
+size_t solve_bytes_mesh(const dg_mesh& m);
+// device data of the hierarchy (levels' heights and diagonals, coarse inverse)
+int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
 int64_t batch_workspace_bytes(int n);
-size_t solve_bytes_n(int64_t n_p);  // device workspace of dg_solve_poisson for n_p pressure unknowns
+
 int launch_velocity_batched(const dg_mesh* const* meshes, int n, dg_prec prec, const void* const* u, void* const* r,
                             void* ws, size_t ws_bytes, hipStream_t s);
 bool poisson_supported(int np, int nq);

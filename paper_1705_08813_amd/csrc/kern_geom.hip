@@ -82,7 +82,7 @@ __global__ void geom_kernel(int nx, int ny, int nz, double Lx, double Lz, double
   if (gid >= ncell * stride) return;
   const int64_t e = gid / stride;
   const int pt = (int)(gid - e * stride);
-  const int ex = (int)(e % nx), ey = (int)((e / nx) % ny), ez = (int)(e / ((int64_t)nx * ny));
+  const int ex = (int)(e % nx), ey = (int)((e / nx) % ny);
   const bool enr = !fully_periodic && ((ey == 0 && lower_slot >= 0) || (ey == ny - 1 && upper_slot >= 0));
   const int nqyc = enr ? NQY : NQ;
   double* out = geo + gid * 10;

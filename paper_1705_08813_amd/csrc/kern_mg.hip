@@ -1,0 +1,383 @@
+// Geometric multigrid transfers for the pressure operator (preconditioner of
+// the Poisson solve; the transfers are the nodal embedding of the coarse DG
+// space into the fine one and its transpose).
+//
+// A coarse cell of level l+1 covers 2 cells of level l along every coarsened
+// direction.  Prolongation evaluates the coarse polynomial at the fine cells'
+// Gauss-Lobatto nodes, direction by direction:
+//   x, z (uniform halves):   child a maps xi_f to xi_c = (a + xi_f) / 2,
+//   y (tanh-graded pairs):   with r = h_0 / (h_0 + h_1) of the two fine layers,
+//                            child 0: xi_c = r xi_f, child 1: r + (1 - r) xi_f.
+// Restriction of residuals (dual vectors) is the transpose.  One workgroup
+// per coarse cell; every fine entry has a single writer.
+#include <cmath>
+#include <vector>
+
+#include "kern_common.h"
+
+namespace dgwm {
+
+namespace {
+
+// N_i(x) of the NP-node Lobatto basis
+template <int NP>
+__device__ __forceinline__ double lobatto_basis(int i, double x) {
+  constexpr auto& L = ct::lobatto<NP>;
+  double v = 1.0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+    if (j != i) v *= (x - L.x[j]) / (L.x[i] - L.x[j]);
+  return v;
+}
+
+// 1-D prolongation tables P[d][child][l][i] = N_i(xi_c(child, xi_l)) of the
+// coarse cell (identity along directions that are not coarsened).
+template <typename T, int NP>
+__device__ __forceinline__ void build_transfer_tables(T* P, int cx, int cy, int cz, double ry) {
+  constexpr auto& L = ct::lobatto<NP>;
+  for (int t = threadIdx.x; t < 3 * 2 * NP * NP; t += blockDim.x) {
+    const int i = t % NP, l = (t / NP) % NP, ch = (t / (NP * NP)) % 2, d = t / (2 * NP * NP);
+    const int c = d == 0 ? cx : (d == 1 ? cy : cz);
+    double v;
+    if (!c) {
+      v = (l == i) ? 1.0 : 0.0;
+    } else {
+      double xc;
+      if (d == 1)
+        xc = ch == 0 ? ry * L.x[l] : ry + (1.0 - ry) * L.x[l];
+      else
+        xc = 0.5 * (ch + L.x[l]);
+      v = lobatto_basis<NP>(i, xc);
+    }
+    P[t] = T(v);
+  }
+}
+
+struct Tr {
+  int nfx, nfy, nfz;   // fine level size
+  int ncx, ncy, ncz;   // coarse level size
+  int cx, cy, cz;
+  const double* hyf;   // fine heights
+};
+
+// rc = P^T rf on one coarse cell
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_restrict_kernel(const Tr tr, const T* __restrict__ rf, T* __restrict__ rc) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
+  __shared__ T P[3 * 2 * NP * NP];
+  __shared__ T F[8 * NP3];  // [c][b][a][k][j][l]
+  __shared__ T G[4 * NP3];  // [c][b][k][j][i]
+  __shared__ T H[2 * NP3];  // [c][k][jc][i]
+  const int64_t C = blockIdx.x;
+  const int X = (int)(C % tr.ncx), Y = (int)((C / tr.ncx) % tr.ncy), Z = (int)(C / ((int64_t)tr.ncx * tr.ncy));
+  const int na = 1 + tr.cx, nb = 1 + tr.cy, nc = 1 + tr.cz;
+  const double ry = tr.cy ? tr.hyf[2 * Y] / (tr.hyf[2 * Y] + tr.hyf[2 * Y + 1]) : 0.5;
+  build_transfer_tables<T, NP>(P, tr.cx, tr.cy, tr.cz, ry);
+  for (int t = threadIdx.x; t < na * nb * nc * NP3; t += blockDim.x) {
+    const int node = t % NP3, ch = t / NP3;
+    const int a = ch % na, b = (ch / na) % nb, c = ch / (na * nb);
+    const int fx = tr.cx ? 2 * X + a : X, fy = tr.cy ? 2 * Y + b : Y, fz = tr.cz ? 2 * Z + c : Z;
+    const int64_t fe = fx + (int64_t)tr.nfx * (fy + (int64_t)tr.nfy * fz);
+    F[((c * 2 + b) * 2 + a) * NP3 + node] = rf[fe * NP3 + node];
+  }
+  __syncthreads();
+  const T* Px = P;
+  const T* Py = P + 2 * NP2;
+  const T* Pz = P + 4 * NP2;
+  // x: G[c][b][k][j][i] = sum_a sum_l Px[a][l][i] F[c][b][a][k][j][l]
+  for (int t = threadIdx.x; t < nc * nb * NP3; t += blockDim.x) {
+    const int i = t % NP, kj = (t / NP) % NP2, cb = t / NP3;
+    const int b = cb % nb, c = cb / nb;
+    T s = 0;
+    for (int a = 0; a < na; ++a) {
+      const T* f = F + ((c * 2 + b) * 2 + a) * NP3 + kj * NP;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) s += Px[(a * NP + l) * NP + i] * f[l];
+    }
+    G[(c * 2 + b) * NP3 + kj * NP + i] = s;
+  }
+  __syncthreads();
+  // y: H[c][k][jc][i] = sum_b sum_m Py[b][m][jc] G[c][b][k][m][i]
+  for (int t = threadIdx.x; t < nc * NP3; t += blockDim.x) {
+    const int i = t % NP, jc = (t / NP) % NP, k = (t / NP2) % NP, c = t / NP3;
+    T s = 0;
+    for (int b = 0; b < nb; ++b) {
+      const T* g = G + (c * 2 + b) * NP3 + k * NP2 + i;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) s += Py[(b * NP + m) * NP + jc] * g[m * NP];
+    }
+    H[c * NP3 + k * NP2 + jc * NP + i] = s;
+  }
+  __syncthreads();
+  // z: rc[kc][jc][i] = sum_c sum_n Pz[c][n][kc] H[c][n][jc][i]
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) {
+    const int ji = t % NP2, kc = t / NP2;
+    T s = 0;
+    for (int c = 0; c < nc; ++c) {
+      const T* h = H + c * NP3 + ji;
+#pragma unroll
+      for (int n = 0; n < NP; ++n) s += Pz[(c * NP + n) * NP + kc] * h[n * NP2];
+    }
+    rc[C * NP3 + t] = s;
+  }
+}
+
+// xf += P xc on the fine cells of one coarse cell
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* __restrict__ xc, T* __restrict__ xf) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
+  __shared__ T P[3 * 2 * NP * NP];
+  __shared__ T S[NP3];      // [kc][jc][i]
+  __shared__ T A[2 * NP3];  // [c][n][jc][i]
+  __shared__ T B[4 * NP3];  // [c][b][n][m][i]
+  const int64_t C = blockIdx.x;
+  const int X = (int)(C % tr.ncx), Y = (int)((C / tr.ncx) % tr.ncy), Z = (int)(C / ((int64_t)tr.ncx * tr.ncy));
+  const int na = 1 + tr.cx, nb = 1 + tr.cy, nc = 1 + tr.cz;
+  const double ry = tr.cy ? tr.hyf[2 * Y] / (tr.hyf[2 * Y] + tr.hyf[2 * Y + 1]) : 0.5;
+  build_transfer_tables<T, NP>(P, tr.cx, tr.cy, tr.cz, ry);
+  for (int t = threadIdx.x; t < NP3; t += blockDim.x) S[t] = xc[C * NP3 + t];
+  __syncthreads();
+  const T* Px = P;
+  const T* Py = P + 2 * NP2;
+  const T* Pz = P + 4 * NP2;
+  for (int t = threadIdx.x; t < nc * NP3; t += blockDim.x) {
+    const int ji = t % NP2, n = (t / NP2) % NP, c = t / NP3;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) s += Pz[(c * NP + n) * NP + k] * S[k * NP2 + ji];
+    A[c * NP3 + n * NP2 + ji] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nc * nb * NP3; t += blockDim.x) {
+    const int i = t % NP, m = (t / NP) % NP, n = (t / NP2) % NP, cb = t / NP3;
+    const int b = cb % nb, c = cb / nb;
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) s += Py[(b * NP + m) * NP + j] * A[c * NP3 + n * NP2 + j * NP + i];
+    B[(c * 2 + b) * NP3 + n * NP2 + m * NP + i] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < na * nb * nc * NP3; t += blockDim.x) {
+    const int node = t % NP3, ch = t / NP3;
+    const int a = ch % na, b = (ch / na) % nb, c = ch / (na * nb);
+    const int l = node % NP, nm = node / NP;
+    T s = 0;
+    const T* bb = B + (c * 2 + b) * NP3 + nm * NP;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) s += Px[(a * NP + l) * NP + i] * bb[i];
+    const int fx = tr.cx ? 2 * X + a : X, fy = tr.cy ? 2 * Y + b : Y, fz = tr.cz ? 2 * Z + c : Z;
+    const int64_t fe = fx + (int64_t)tr.nfx * (fy + (int64_t)tr.nfy * fz);
+    xf[fe * NP3 + node] += s;
+  }
+}
+
+// x = B b for a dense symmetric B (n x n), one thread per entry of x
+template <typename T>
+__global__ __launch_bounds__(256) void dense_apply_kernel(int64_t n, const T* __restrict__ B, const T* __restrict__ b,
+                                                          T* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int64_t j = 0; j < n; ++j) s += B[j * n + i] * b[j];
+  x[i] = s;
+}
+
+// columns of the n x n identity, one vector of n entries per column
+__global__ void identity_kernel(double* __restrict__ E, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n * n; t += (int64_t)gridDim.x * blockDim.x)
+    E[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
+__global__ void to_f32_kernel(float* __restrict__ o, const double* __restrict__ a, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    o[t] = (float)a[t];
+}
+
+Tr make_tr(const dg_mesh* m, int l) {
+  const MgLevel& f = m->mg[l];
+  const MgLevel& c = m->mg[l + 1];
+  Tr t;
+  t.nfx = f.nx;
+  t.nfy = f.ny;
+  t.nfz = f.nz;
+  t.ncx = c.nx;
+  t.ncy = c.ny;
+  t.ncz = c.nz;
+  t.cx = c.cx;
+  t.cy = c.cy;
+  t.cz = c.cz;
+  t.hyf = f.hy;
+  return t;
+}
+
+}  // namespace
+
+#define DG_MG_NP(X) X(2) X(3) X(4) X(5) X(6)
+
+int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s) {
+  const Tr tr = make_tr(m, l);
+  const unsigned nb = (unsigned)m->mg[l + 1].ncell;
+#define X(a)                                                                                                  \
+  if (m->np_p == a) {                                                                                         \
+    if (prec == DG_F64)                                                                                       \
+      hipLaunchKernelGGL((mg_restrict_kernel<double, a>), dim3(nb), dim3(256), 0, s, tr,                      \
+                         static_cast<const double*>(rf), static_cast<double*>(rc));                           \
+    else                                                                                                      \
+      hipLaunchKernelGGL((mg_restrict_kernel<float, a>), dim3(nb), dim3(256), 0, s, tr,                       \
+                         static_cast<const float*>(rf), static_cast<float*>(rc));                             \
+    return check_hip(hipGetLastError(), "restriction launch");                                                \
+  }
+  DG_MG_NP(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "multigrid transfer degree not compiled");
+}
+
+int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, void* xf, hipStream_t s) {
+  const Tr tr = make_tr(m, l);
+  const unsigned nb = (unsigned)m->mg[l + 1].ncell;
+#define X(a)                                                                                                  \
+  if (m->np_p == a) {                                                                                         \
+    if (prec == DG_F64)                                                                                       \
+      hipLaunchKernelGGL((mg_prolong_kernel<double, a>), dim3(nb), dim3(256), 0, s, tr,                       \
+                         static_cast<const double*>(xc), static_cast<double*>(xf));                           \
+    else                                                                                                      \
+      hipLaunchKernelGGL((mg_prolong_kernel<float, a>), dim3(nb), dim3(256), 0, s, tr,                        \
+                         static_cast<const float*>(xc), static_cast<float*>(xf));                             \
+    return check_hip(hipGetLastError(), "prolongation launch");                                               \
+  }
+  DG_MG_NP(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "multigrid transfer degree not compiled");
+}
+
+int launch_dense_apply(int64_t n, dg_prec prec, const void* B, const void* b, void* x, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (prec == DG_F64)
+    hipLaunchKernelGGL((dense_apply_kernel<double>), dim3(nb), dim3(256), 0, s, n, static_cast<const double*>(B),
+                       static_cast<const double*>(b), static_cast<double*>(x));
+  else
+    hipLaunchKernelGGL((dense_apply_kernel<float>), dim3(nb), dim3(256), 0, s, n, static_cast<const float*>(B),
+                       static_cast<const float*>(b), static_cast<float*>(x));
+  return check_hip(hipGetLastError(), "dense apply launch");
+}
+
+// Levels of a box mesh (host).
+int mg_plan(const dg_mesh_params& P, MgLevel* lv) {
+  const int np = P.k_p + 1;
+  const int64_t np3 = (int64_t)np * np * np;
+  int n = 1;
+  lv[0] = MgLevel{};
+  lv[0].nx = P.nx;
+  lv[0].ny = P.ny;
+  lv[0].nz = P.nz;
+  lv[0].ncell = (int64_t)P.nx * P.ny * P.nz;
+  lv[0].n = lv[0].ncell * np3;
+  lv[0].hx = P.Lx / P.nx;
+  lv[0].hz = P.Lz / P.nz;
+  while (n < kMaxLevels) {
+    const MgLevel& f = lv[n - 1];
+    if (f.n <= kCoarseTarget) break;  // small enough for the dense coarse solve
+    const int cx = (f.nx % 2 == 0) ? 1 : 0;
+    const int cy = (f.ny % 2 == 0 && (P.fully_periodic ? f.ny >= 2 : f.ny >= 4)) ? 1 : 0;
+    const int cz = (f.nz % 2 == 0) ? 1 : 0;
+    if (!cx && !cy && !cz) break;
+    MgLevel c{};
+    c.cx = cx;
+    c.cy = cy;
+    c.cz = cz;
+    c.nx = cx ? f.nx / 2 : f.nx;
+    c.ny = cy ? f.ny / 2 : f.ny;
+    c.nz = cz ? f.nz / 2 : f.nz;
+    c.ncell = (int64_t)c.nx * c.ny * c.nz;
+    c.n = c.ncell * np3;
+    c.hx = P.Lx / c.nx;
+    c.hz = P.Lz / c.nz;
+    lv[n++] = c;
+  }
+  return n;
+}
+
+// Device data of the hierarchy (the pointers of m->mg[] and coarse_inv are
+// set by the caller): wall-normal heights of every level from every second
+// vertex, Jacobi diagonals, and the pseudo-inverse of the coarsest operator.
+// coarse_scr holds 2 n_c^2 doubles of scratch for the assembly.
+int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s) {
+  int rc = DG_OK;
+  std::vector<std::vector<double>> hys(m->mg_nlev);
+  std::vector<double> eta = eta0;
+  for (int l = 1; l < m->mg_nlev && !rc; ++l) {
+    const MgLevel& c = m->mg[l];
+    if (c.cy) {
+      std::vector<double> e2(c.ny + 1);
+      for (int j = 0; j <= c.ny; ++j) e2[j] = eta[2 * j];
+      eta.swap(e2);
+    }
+    hys[l].resize(c.ny);
+    for (int j = 0; j < c.ny; ++j) hys[l][j] = eta[j + 1] - eta[j];
+    rc = check_hip(hipMemcpyAsync(m->mg[l].hy, hys[l].data(), sizeof(double) * c.ny, hipMemcpyHostToDevice, s),
+                   "level heights");
+    if (!rc) rc = launch_poisson_diag_level(m, l, s);
+  }
+  if (rc || !m->coarse_inv) {
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "multigrid setup");
+    return rc;
+  }
+  // coarsest operator column by column (A is symmetric), then
+  // B = (A + alpha 1 1^T)^{-1}: for b with zero mean, x = B b is the
+  // zero-mean solution of A x = b
+  const int L = m->mg_nlev - 1;
+  const int64_t n = m->mg[L].n;
+  double* E = coarse_scr;
+  double* Y = coarse_scr + n * n;
+  hipLaunchKernelGGL(identity_kernel, dim3(256), dim3(256), 0, s, E, n);
+  rc = launch_poisson_level(m, L, DG_F64, E, Y, s, (int)n, n);
+  std::vector<double> A(n * n);
+  if (!rc) rc = check_hip(hipMemcpyAsync(A.data(), Y, sizeof(double) * n * n, hipMemcpyDeviceToHost, s), "coarse copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "coarse assembly");
+  if (rc) return rc;
+  double tr = 0;
+  for (int64_t i = 0; i < n; ++i) tr += A[i * n + i];
+  const double alpha = tr / ((double)n * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) {
+      const double v = 0.5 * (A[i * n + j] + A[j * n + i]);
+      A[i * n + j] = A[j * n + i] = v;
+    }
+  for (int64_t t = 0; t < n * n; ++t) A[t] += alpha;
+  // Cholesky A = L L^T (lower, in place), then B = L^{-T} L^{-1}
+  for (int64_t j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0)) return set_error(DG_ERR_NONFINITE, "coarsest operator is not positive definite");
+    d = std::sqrt(d);
+    A[j * n + j] = d;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int64_t k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = v / d;
+    }
+  }
+  std::vector<double> Li(n * n, 0.0);  // L^{-1}, lower
+  for (int64_t j = 0; j < n; ++j) {
+    Li[j * n + j] = 1.0 / A[j * n + j];
+    for (int64_t i = j + 1; i < n; ++i) {
+      double v = 0;
+      for (int64_t k = j; k < i; ++k) v -= A[i * n + k] * Li[k * n + j];
+      Li[i * n + j] = v / A[i * n + i];
+    }
+  }
+  std::vector<double> B(n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      double v = 0;
+      for (int64_t k = i; k < n; ++k) v += Li[k * n + i] * Li[k * n + j];
+      B[i * n + j] = B[j * n + i] = v;
+    }
+  rc = check_hip(hipMemcpyAsync(m->coarse_inv, B.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s),
+                 "coarse inverse");
+  if (!rc) hipLaunchKernelGGL(to_f32_kernel, dim3(256), dim3(256), 0, s, m->coarse_inv32, m->coarse_inv, n * n);
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "multigrid setup");
+  return rc;
+}
+
+}  // namespace dgwm

@@ -63,8 +63,11 @@ __device__ __forceinline__ constexpr int pencil_stride(int D) {
 // one writer).
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y,
-                                                      int64_t ncell, int nblocks) {
+                                                      int64_t ncell, int nblocks, int64_t vstride) {
   using BL = PoiBlk<NP>;
+  // blockIdx.y selects one of several vectors stored vstride apart
+  p += blockIdx.y * vstride;
+  y += blockIdx.y * vstride;
   constexpr int NP2 = BL::NP2, NP3 = BL::NP3, CB = BL::CB;
   __shared__ T s_P[CB * NP3];
   __shared__ T s_X[CB * NP3];
@@ -323,18 +326,20 @@ __global__ void poisson_diag_kernel(const MeshDev M, int64_t ncell, double* __re
   dg32[gid] = (float)acc;
 }
 
-MeshDev make_meshdev_p(const dg_mesh* m) {
+// Mesh arguments of multigrid level l (level 0: the mesh itself).
+MeshDev make_meshdev_p(const dg_mesh* m, int l = 0) {
   MeshDev M{};
-  M.nx = m->P.nx;
-  M.ny = m->P.ny;
-  M.nz = m->P.nz;
+  const MgLevel* lv = (l > 0) ? &m->mg[l] : nullptr;
+  M.nx = lv ? lv->nx : m->P.nx;
+  M.ny = lv ? lv->ny : m->P.ny;
+  M.nz = lv ? lv->nz : m->P.nz;
   M.fully_periodic = m->P.fully_periodic;
   M.lower_slot = m->lower_slot;
   M.upper_slot = m->upper_slot;
   M.nslots = m->n_enr_layers;
-  M.hx = m->hx;
-  M.hz = m->hz;
-  M.hy = m->hy;
+  M.hx = lv ? lv->hx : m->hx;
+  M.hz = lv ? lv->hz : m->hz;
+  M.hy = lv ? lv->hy : m->hy;
   M.tab = m->tab_p;
   M.ops_off = tab_layout(m->np_p, m->P.nq_p, m->P.nq_p).size;
   M.pen = m->P.ip_factor_p * (m->P.k_p + 1.0) * (m->P.k_p + 1.0);
@@ -355,17 +360,19 @@ bool poisson_supported(int np, int nq) {
 
 const char* poisson_combos() { return "poisson (k+1, nq_p): (2,2) (3,3) (4,4) (5,5) (6,6)"; }
 
-int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s) {
-  const MeshDev M = make_meshdev_p(m);
+int launch_poisson_level(const dg_mesh* m, int l, dg_prec prec, const void* p, void* y, hipStream_t s, int nvec,
+                         int64_t vstride) {
+  const MeshDev M = make_meshdev_p(m, l);
+  const int64_t ncell = l > 0 ? m->mg[l].ncell : m->ncell;
 #define X(a, b)                                                                                           \
   if (m->np_p == a && m->P.nq_p == b) {                                                                   \
-    const int nb = (int)((m->ncell + PoiBlk<a>::CB - 1) / PoiBlk<a>::CB);                                 \
+    const int nb = (int)((ncell + PoiBlk<a>::CB - 1) / PoiBlk<a>::CB);                                    \
     if (prec == DG_F64)                                                                                   \
-      hipLaunchKernelGGL((poisson_kernel<double, a>), dim3(nb), dim3(256), 0, s, M,                       \
-                         static_cast<const double*>(p), static_cast<double*>(y), m->ncell, nb);           \
+      hipLaunchKernelGGL((poisson_kernel<double, a>), dim3(nb, nvec), dim3(256), 0, s, M,                 \
+                         static_cast<const double*>(p), static_cast<double*>(y), ncell, nb, vstride);     \
     else                                                                                                  \
-      hipLaunchKernelGGL((poisson_kernel<float, a>), dim3(nb), dim3(256), 0, s, M,                        \
-                         static_cast<const float*>(p), static_cast<float*>(y), m->ncell, nb);             \
+      hipLaunchKernelGGL((poisson_kernel<float, a>), dim3(nb, nvec), dim3(256), 0, s, M,                  \
+                         static_cast<const float*>(p), static_cast<float*>(y), ncell, nb, vstride);       \
     return check_hip(hipGetLastError(), "poisson kernel launch");                                         \
   }
   DG_POI_COMBOS(X)
@@ -373,19 +380,27 @@ int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipSt
   return set_error(DG_ERR_UNSUPPORTED, "poisson degree/quadrature combination not compiled");
 }
 
-int launch_poisson_diag(const dg_mesh* m, hipStream_t s) {
-  const MeshDev M = make_meshdev_p(m);
-  const int64_t n = m->n_p;
+int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s) {
+  return launch_poisson_level(m, 0, prec, p, y, s);
+}
+
+int launch_poisson_diag_level(const dg_mesh* m, int l, hipStream_t s) {
+  const MeshDev M = make_meshdev_p(m, l);
+  const int64_t ncell = l > 0 ? m->mg[l].ncell : m->ncell;
+  const int64_t n = l > 0 ? m->mg[l].n : m->n_p;
+  double* dg = l > 0 ? m->mg[l].diag : m->diag;
+  float* dg32 = l > 0 ? m->mg[l].diag32 : m->diag32;
   const unsigned nb = (unsigned)((n + 255) / 256);
 #define X(a, b)                                                                                           \
   if (m->np_p == a && m->P.nq_p == b) {                                                                   \
-    hipLaunchKernelGGL((poisson_diag_kernel<a, b>), dim3(nb), dim3(256), 0, s, M, m->ncell, m->diag,      \
-                       m->diag32);                                                                        \
+    hipLaunchKernelGGL((poisson_diag_kernel<a, b>), dim3(nb), dim3(256), 0, s, M, ncell, dg, dg32);       \
     return check_hip(hipGetLastError(), "poisson diagonal launch");                                       \
   }
   DG_POI_COMBOS(X)
 #undef X
   return set_error(DG_ERR_UNSUPPORTED, "poisson degree/quadrature combination not compiled");
 }
+
+int launch_poisson_diag(const dg_mesh* m, hipStream_t s) { return launch_poisson_diag_level(m, 0, s); }
 
 }  // namespace dgwm

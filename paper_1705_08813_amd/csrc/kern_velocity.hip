@@ -82,44 +82,78 @@ __device__ __forceinline__ FaceNb face_nb(const MeshDev& M, int ex, int ey, int 
 }
 
 // Neighbour face layers of all six faces: value and normal derivative of each
-// component on the neighbour's node layer at the shared face.  One global
-// read per neighbour node; all six faces are fetched in one phase.
-template <typename T, int NP, bool REF>
-__device__ __forceinline__ void load_neighbour_layers(const MeshDev& M, const T* __restrict__ u, T* s_nl, T* s_nut,
-                                                      const double* tab_nd0, const double* tab_nd1, int ex, int ey,
-                                                      int ez, bool need_nut) {
-  constexpr int NP2 = NP * NP, NP3 = NP * NP * NP;
-  for (int t = threadIdx.x; t < 6 * 3 * NP2; t += 256) {
-    const int f = t / (3 * NP2), rem = t - f * 3 * NP2;
-    const int c = rem / NP2, k = rem - c * NP2;
-    const int D = f >> 1, S = f & 1;
-    const FaceNb nb = face_nb(M, ex, ey, ez, D, S);
-    T val = 0, der = 0;
-    if (!nb.wall) {
-      int base, stride;
-      line_of<NP>(D, k % NP, k / NP, base, stride);
-      const double* nd = S ? tab_nd0 : tab_nd1;  // neighbour's face is at xi_D = 1 - S
-      const int lface = S ? 0 : NP - 1;
-      const T* src = u + (nb.enb * 3 + c) * NP3 + base;
-      T x[NP];
+// component on the neighbour's node layer at the shared face.  The lines of
+// neighbour nodes are fetched into registers when the cell starts (nb_fetch),
+// so their latency overlaps the volume term, and reduced to value and
+// derivative into LDS right before the face phases (nb_store).
+template <typename T, int NP>
+struct NbLines {
+  static constexpr int NP2 = NP * NP, N = 6 * 3 * NP2, ITEMS = (N + 255) / 256;
+  T x[ITEMS][NP];
+  T nut;  // enrichment coefficient of a neighbour (threads 0..17: face f = tid / 3, component tid % 3)
+};
+
+template <typename T, int NP>
+__device__ __forceinline__ void nb_fetch(const MeshDev& M, const T* __restrict__ u, int ex, int ey, int ez,
+                                         NbLines<T, NP>& L) {
+  using NL = NbLines<T, NP>;
+  constexpr int NP2 = NL::NP2, NP3 = NP * NP * NP;
 #pragma unroll
-      for (int l = 0; l < NP; ++l) x[l] = src[l * stride];
+  for (int it = 0; it < NL::ITEMS; ++it) {
+    const int t = threadIdx.x + 256 * it;
 #pragma unroll
-      for (int l = 0; l < NP; ++l) der += T(nd[l]) * x[l];
-      val = x[lface];
-      if (!REF) {  // affine cells: physical normal derivative
-        const T hdn = D == 0 ? T(M.hx) : (D == 1 ? T(M.hy[nb.nidx1]) : T(M.hz));
-        der /= hdn;
+    for (int l = 0; l < NP; ++l) L.x[it][l] = 0;
+    if (t < NL::N) {
+      const int f = t / (3 * NP2), rem = t - f * 3 * NP2;
+      const int c = rem / NP2, k = rem - c * NP2;
+      const FaceNb nb = face_nb(M, ex, ey, ez, f >> 1, f & 1);
+      if (!nb.wall) {
+        int base, stride;
+        line_of<NP>(f >> 1, k % NP, k / NP, base, stride);
+        const T* src = u + (nb.enb * 3 + c) * NP3 + base;
+#pragma unroll
+        for (int l = 0; l < NP; ++l) L.x[it][l] = src[l * stride];
       }
     }
-    s_nl[((f * 3 + c) * 2 + 0) * NP2 + k] = val;
-    s_nl[((f * 3 + c) * 2 + 1) * NP2 + k] = der;
   }
-  if (need_nut && threadIdx.x < 18) {
+  L.nut = 0;
+  if (threadIdx.x < 18) {
     const int f = threadIdx.x / 3, c = threadIdx.x % 3;
     const FaceNb nb = face_nb(M, ex, ey, ez, f >> 1, f & 1);
-    s_nut[threadIdx.x] = nb.enr_nb >= 0 ? u[M.enr_off + nb.enr_nb * 3 + c] : T(0);
+    if (nb.enr_nb >= 0) L.nut = u[M.enr_off + nb.enr_nb * 3 + c];
   }
+}
+
+template <typename T, int NP, int NQ, bool REF>
+__device__ __forceinline__ void nb_store(const MeshDev& M, const NbLines<T, NP>& L, T* s_nl, T* s_nut, int ex, int ey,
+                                         int ez) {
+  using NL = NbLines<T, NP>;
+  constexpr int NP2 = NL::NP2;
+  constexpr auto& tb = ct::tab<NP, NQ>;
+#pragma unroll
+  for (int it = 0; it < NL::ITEMS; ++it) {
+    const int t = threadIdx.x + 256 * it;
+    if (t < NL::N) {
+      const int f = t / (3 * NP2), rem = t - f * 3 * NP2;
+      const int c = rem / NP2, k = rem - c * NP2;
+      const int D = f >> 1, S = f & 1;
+      T val = 0, der = 0;
+      const FaceNb nb = face_nb(M, ex, ey, ez, D, S);
+      if (!nb.wall) {
+        // the neighbour's face is at xi_D = 1 - S
+#pragma unroll
+        for (int l = 0; l < NP; ++l) der += T(S ? tb.nd0[l] : tb.nd1[l]) * L.x[it][l];
+        val = S ? L.x[it][0] : L.x[it][NP - 1];
+        if (!REF) {  // affine cells: physical normal derivative
+          const T hdn = D == 0 ? T(M.hx) : (D == 1 ? T(M.hy[nb.nidx1]) : T(M.hz));
+          der /= hdn;
+        }
+      }
+      s_nl[((f * 3 + c) * 2 + 0) * NP2 + k] = val;
+      s_nl[((f * 3 + c) * 2 + 1) * NP2 + k] = der;
+    }
+  }
+  if (threadIdx.x < 18) s_nut[threadIdx.x] = L.nut;
 }
 
 // 1-D tables used by the face phases, staged in LDS in the working precision
@@ -172,7 +206,6 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   constexpr int Q2 = T2 == 1 ? NQY : NQ;
   constexpr int FP = Q1 * Q2;
   constexpr int NP2 = Sh::NP2, NP3 = Sh::NP3;
-  constexpr int QN = Q1 * NP;
   constexpr auto& tb1 = ct::tab<NP, Q1>;
   constexpr auto& tb2 = ct::tab<NP, Q2>;
   constexpr auto& tbn = ct::tab<NP, NQ>;  // nd0, nd1 do not depend on the rule
@@ -727,7 +760,6 @@ template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
 __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
                                          int layer_lo, int nlayers) {
   using Sh = VelShape<T, NP, NQ, NQY>;
-  constexpr TabLayout L = tab_layout(NP, NQ, NQY);
   constexpr int NP3 = Sh::NP3, NPTS = Sh::NPTS;
   __shared__ T s_u[3 * NP3];
   __shared__ T s_r[3 * NP3];
@@ -769,6 +801,8 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
 
   for (int i = tid; i < 3 * NP3; i += nt) s_u[i] = u[e * 3 * NP3 + i];
   if (ENR && tid < 3) s_ut[tid] = u[M.enr_off + enr * 3 + tid];
+  NbLines<T, NP> nbl;
+  nb_fetch<T, NP>(M, u, ex, ey, ez, nbl);
   if (CURVED) load_face_tab<T, NP, NQ, NQY, ENR>(tab, s_tab);
   __syncthreads();
 
@@ -873,7 +907,7 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   // faces: neighbour layers of all six faces (one phase), then each direction
   T* s_nl = s_big;
   T* s_face = s_big + Sh::NL;
-  load_neighbour_layers<T, NP, CURVED>(M, u, s_nl, s_nut, tab + L.nd0, tab + L.nd1, ex, ey, ez, true);
+  nb_store<T, NP, NQ, CURVED>(M, nbl, s_nl, s_nut, ex, ey, ez);
   __syncthreads();
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 0>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,

@@ -25,6 +25,7 @@ namespace dgwm {
 namespace {
 
 constexpr int kRedBlocks = 512;
+constexpr double kSmoothRange = 20.0;  // multigrid smoother interval [lmax / 20, 1.1 lmax]
 constexpr int kRedThreads = 256;
 
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
@@ -141,6 +142,24 @@ __global__ void k_cheb_step(T* __restrict__ z, T* __restrict__ d, const T* __res
   }
 }
 
+// Chebyshev first step from a non-zero start: d = c Dinv (b - Ax), x += d
+template <typename T>
+__global__ void k_cheb_first_res(T* __restrict__ x, T* __restrict__ d, const T* __restrict__ b,
+                                 const T* __restrict__ ax, const T* __restrict__ dinv, int64_t n, T c) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T v = c * dinv[i] * (b[i] - ax[i]);
+    d[i] = v;
+    x[i] += v;
+  }
+}
+
+// r = b - Ax in the working precision
+template <typename T>
+__global__ void k_resid_t(T* __restrict__ r, const T* __restrict__ b, const T* __restrict__ ax, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = b[i] - ax[i];
+}
+
 // out32 = r / sqrt(rr)
 __global__ void k_to_f32(float* __restrict__ out, const double* __restrict__ r, int64_t n,
                          const double* __restrict__ rr) {
@@ -227,16 +246,17 @@ struct Solver {
     return check_hip(hipGetLastError(), "reduce");
   }
   template <typename TA, typename TB>
-  int dot(const TA* a, const TB* b, double* out) {
-    hipLaunchKernelGGL((k_dot<TA, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n, part);
+  int dot(const TA* a, const TB* b, double* out, int64_t nn = -1) {
+    hipLaunchKernelGGL((k_dot<TA, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, nn < 0 ? n : nn, part);
     return red_final(out);
   }
   template <typename T>
-  int project(T* a, double* sum) {
-    hipLaunchKernelGGL((k_sum<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, n, part);
+  int project(T* a, double* sum, int64_t nn = -1) {
+    if (nn < 0) nn = n;
+    hipLaunchKernelGGL((k_sum<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, nn, part);
     int rc = red_final(sum);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_sub_mean<T>), dim3(grid), dim3(256), 0, s, a, n, sum);
+    hipLaunchKernelGGL((k_sub_mean<T>), dim3(grid_of(nn)), dim3(256), 0, s, a, nn, sum);
     return check_hip(hipGetLastError(), "sub mean");
   }
   int A64(const double* x, double* y) {
@@ -247,6 +267,108 @@ struct Solver {
     ++applies32;
     return launch_poisson(m, DG_F32, x, y, s);
   }
+  // ---- multigrid (levels 1.. of the mesh hierarchy) ----
+  struct Lv {
+    char* x;
+    char* b;
+    char* r;
+    char* d;
+    char* t;
+    double* dinv64;
+    float* dinv32;
+    int64_t n;
+  };
+  Lv lv[kMaxLevels];
+  int nlev = 0;
+  static unsigned grid_of(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 2048); }
+  template <typename T>
+  int Alev(int l, const T* x, T* y) {
+    if (l == 0) {
+      if (sizeof(T) == 8) ++applies64; else ++applies32;
+    }
+    return launch_poisson_level(m, l, sizeof(T) == 8 ? DG_F64 : DG_F32, x, y, s);
+  }
+  template <typename T>
+  const T* dinv_of(int l) {
+    if (sizeof(T) == 8) return reinterpret_cast<const T*>(l == 0 ? dinv : lv[l].dinv64);
+    return reinterpret_cast<const T*>(l == 0 ? dinv32 : lv[l].dinv32);
+  }
+  int64_t n_of(int l) const { return l == 0 ? n : lv[l].n; }
+  // z = Cheb_m(D^{-1} A_l) D^{-1} r from a zero start (m - 1 operator applications)
+  template <typename T>
+  int cheb_l(int l, T* zz, const T* rr, T* dd, T* tt, int deg, double lmin, double lmax) {
+    const int64_t nn = n_of(l);
+    const unsigned g = grid_of(nn);
+    const T* di = dinv_of<T>(l);
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    hipLaunchKernelGGL((k_cheb_first<T>), dim3(g), dim3(256), 0, s, zz, dd, rr, di, nn, (T)(1.0 / theta));
+    for (int k = 1; k < deg; ++k) {
+      int rc = Alev<T>(l, zz, tt);
+      if (rc) return rc;
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      hipLaunchKernelGGL((k_cheb_step<T>), dim3(g), dim3(256), 0, s, zz, dd, rr, tt, di, nn, (T)(rho_new * rho),
+                         (T)(2.0 * rho_new / delta));
+      rho = rho_new;
+    }
+    return check_hip(hipGetLastError(), "chebyshev");
+  }
+  // the same polynomial continued from the current x (m operator applications)
+  template <typename T>
+  int cheb_from(int l, T* xx, const T* bb, T* dd, T* tt, int deg, double lmin, double lmax) {
+    const int64_t nn = n_of(l);
+    const unsigned g = grid_of(nn);
+    const T* di = dinv_of<T>(l);
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    int rc = Alev<T>(l, xx, tt);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_cheb_first_res<T>), dim3(g), dim3(256), 0, s, xx, dd, bb, tt, di, nn, (T)(1.0 / theta));
+    for (int k = 1; k < deg; ++k) {
+      if ((rc = Alev<T>(l, xx, tt))) return rc;
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      hipLaunchKernelGGL((k_cheb_step<T>), dim3(g), dim3(256), 0, s, xx, dd, bb, tt, di, nn, (T)(rho_new * rho),
+                         (T)(2.0 * rho_new / delta));
+      rho = rho_new;
+    }
+    return check_hip(hipGetLastError(), "chebyshev");
+  }
+  // x = V-cycle(l) b: Chebyshev-Jacobi pre-smoothing, restricted residual,
+  // coarse correction, post-smoothing; the coarsest level is solved with the
+  // dense pseudo-inverse (or smoothed with a long polynomial).
+  template <typename T>
+  int vcycle(int l, T* x, const T* b, T* r, T* d, T* t, int deg) {
+    const dg_mesh* mm = m;
+    const int L = nlev - 1;
+    const int64_t nn = n_of(l);
+    const unsigned g = grid_of(nn);
+    const double lam = mm->mg[l].lam;
+    const dg_prec prec = sizeof(T) == 8 ? DG_F64 : DG_F32;
+    int rc;
+    if (l == L) {
+      if (mm->coarse_inv)
+        return launch_dense_apply(nn, prec, sizeof(T) == 8 ? (const void*)mm->coarse_inv : (const void*)mm->coarse_inv32,
+                                  b, x, s);
+      return cheb_l<T>(l, x, b, d, t, 4 * deg, lam / 200.0, 1.1 * lam);
+    }
+    const double lmin = lam / kSmoothRange, lmax = 1.1 * lam;
+    if ((rc = cheb_l<T>(l, x, b, d, t, deg, lmin, lmax))) return rc;
+    if ((rc = Alev<T>(l, x, t))) return rc;
+    hipLaunchKernelGGL((k_resid_t<T>), dim3(g), dim3(256), 0, s, r, b, t, nn);
+    Lv& c = lv[l + 1];
+    T* xc = reinterpret_cast<T*>(c.x);
+    T* bc = reinterpret_cast<T*>(c.b);
+    if ((rc = launch_mg_restrict(mm, l, prec, r, bc, s))) return rc;
+    if ((rc = vcycle<T>(l + 1, xc, bc, reinterpret_cast<T*>(c.r), reinterpret_cast<T*>(c.d),
+                        reinterpret_cast<T*>(c.t), deg)))
+      return rc;
+    if ((rc = launch_mg_prolong_add(mm, l, prec, xc, x, s))) return rc;
+    return cheb_from<T>(l, x, b, d, t, deg, lmin, lmax);
+  }
+  // Lanczos estimate of lmax(D^{-1} A_l) (20 Jacobi-PCG steps in FP64 on
+  // level l, using the level-0 work vectors, which are at least as long)
+  int lanczos(int l, double* out);
+
   // blocking read of one device scalar (NaN if the copy fails)
   double host(const double* dev) {
     double h = 0;
@@ -272,6 +394,56 @@ struct Solver {
   }
 };
 
+int Solver::lanczos(int l, double* out) {
+  // 20 Jacobi-PCG steps with every scalar kept on the device (no host
+  // synchronisation inside the loop); the CG coefficients come back in one
+  // copy and give the Lanczos tridiagonal.  A breakdown (exact convergence on
+  // a tiny level) only truncates the valid prefix.
+  constexpr int K = 20;
+  const int64_t nn = n_of(l);
+  const unsigned g = grid_of(nn);
+  const double* di = dinv_of<double>(l);
+  double* RZ = sc + 20;  // sc[20..39]
+  double* PQ = sc + 40;  // sc[40..59]
+  hipLaunchKernelGGL(k_hash_fill, dim3(g), dim3(256), 0, s, r, nn);
+  int rc = project(r, sc + 16, nn);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_fill<double>), dim3(g), dim3(256), 0, s, t64, nn, 0.0);
+  for (int k = 0; k < K; ++k) {
+    hipLaunchKernelGGL((k_cheb_first<double>), dim3(g), dim3(256), 0, s, z, d64, r, di, nn, 1.0);
+    if ((rc = dot(r, z, RZ + k, nn))) return rc;
+    if (k == 0)
+      hipLaunchKernelGGL((k_copy<double>), dim3(g), dim3(256), 0, s, p, z, nn);
+    else
+      hipLaunchKernelGGL((k_update_p<double>), dim3(g), dim3(256), 0, s, p, z, nn, RZ + k, (const double*)nullptr,
+                         RZ + k - 1);
+    if ((rc = launch_poisson_level(m, l, DG_F64, p, q, s))) return rc;
+    if ((rc = dot(p, q, PQ + k, nn))) return rc;
+    hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, t64, r, p, q, nn, RZ + k,
+                       PQ + k, part);
+  }
+  double h[2 * K];
+  if ((rc = check_hip(hipMemcpyAsync(h, RZ, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s), "lanczos copy")))
+    return rc;
+  if ((rc = check_hip(hipStreamSynchronize(s), "lanczos"))) return rc;
+  std::vector<double> al, be;
+  for (int k = 0; k < K; ++k) {
+    const double rz = h[k], pq = h[K + k];
+    if (!(rz > 0) || !(pq > 0) || !std::isfinite(rz) || !std::isfinite(pq)) break;
+    if (k > 0) be.push_back(rz / h[k - 1]);
+    al.push_back(rz / pq);
+  }
+  const int kk = (int)al.size();
+  if (kk < 1) return set_error(DG_ERR_NONFINITE, "eigenvalue estimate failed");
+  std::vector<double> diag(kk), off(kk > 1 ? kk - 1 : 0);
+  for (int j = 0; j < kk; ++j) {
+    diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < kk) off[j] = std::sqrt(be[j]) / al[j];
+  }
+  *out = tridiag_max_eig(diag, off);
+  return DG_OK;
+}
+
 }  // namespace
 }  // namespace dgwm
 
@@ -281,15 +453,20 @@ namespace {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-size_t solve_bytes(const dg_mesh* m) { return dgwm::solve_bytes_n(m->n_p); }
+size_t solve_bytes(const dg_mesh* m) { return dgwm::solve_bytes_mesh(*m); }
 
 }  // namespace
 
 namespace dgwm {
-size_t solve_bytes_n(int64_t n_p) {
-  const size_t n = (size_t)n_p;
-  return 9 * up256(n * sizeof(double)) + 9 * up256(n * sizeof(float)) + up256(64 * sizeof(double)) +
-         up256(kRedBlocks * sizeof(double));
+// 9 FP64 and 9 FP32 vectors of the fine level, scalars and partial sums,
+// then per coarser multigrid level 5 work vectors and the FP64 and FP32
+// inverse diagonals (8 bytes per entry each, so either precision fits).
+size_t solve_bytes_mesh(const dg_mesh& m) {
+  const size_t n = (size_t)m.n_p;
+  size_t b = 9 * up256(n * sizeof(double)) + 9 * up256(n * sizeof(float)) + up256(64 * sizeof(double)) +
+             up256(kRedBlocks * sizeof(double));
+  for (int l = 1; l < m.mg_nlev; ++l) b += 7 * up256((size_t)m.mg[l].n * sizeof(double));
+  return b;
 }
 }  // namespace dgwm
 
@@ -324,6 +501,21 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   S.sc = reinterpret_cast<double*>(w);
   w += up256(64 * sizeof(double));
   S.part = reinterpret_cast<double*>(w);
+  w += up256(kRedBlocks * sizeof(double));
+  const bool use_mg = sp->multigrid && m->mg_nlev > 1;
+  S.nlev = use_mg ? m->mg_nlev : 0;
+  for (int l = 1; l < m->mg_nlev; ++l) {
+    const size_t bytes = up256((size_t)m->mg[l].n * sizeof(double));
+    Solver::Lv& v = S.lv[l];
+    v.n = m->mg[l].n;
+    v.x = w; w += bytes;
+    v.b = w; w += bytes;
+    v.r = w; w += bytes;
+    v.d = w; w += bytes;
+    v.t = w; w += bytes;
+    v.dinv64 = reinterpret_cast<double*>(w); w += bytes;
+    v.dinv32 = reinterpret_cast<float*>(w); w += bytes;
+  }
   double* sc = S.sc;
   enum { RZ0 = 0, RZ1 = 1, PQ = 2, RR = 3, RZX = 4, SUM = 5, NB = 6, IRZ0 = 8, IRZ1 = 9, IPQ = 10, IRR = 11 };
   int rc;
@@ -333,45 +525,21 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   hipLaunchKernelGGL((k_recip<float>), dim3(S.grid), dim3(256), 0, S.s, S.dinv32, m->diag, S.n);
 
   // Chebyshev interval: Lanczos estimate of lmax(D^{-1} A), cached per mesh
+  // (and per multigrid level)
   dg_mesh* mm = const_cast<dg_mesh*>(m);
   if (!(mm->lam_max > 0)) {
-    hipLaunchKernelGGL(k_hash_fill, dim3(S.grid), dim3(256), 0, S.s, S.r, S.n);
-    DG_TRY(S.project(S.r, sc + SUM));
-    hipLaunchKernelGGL((k_fill<double>), dim3(S.grid), dim3(256), 0, S.s, S.t64, S.n, 0.0);
-    std::vector<double> al, be;
-    double rz_old = 0;
-    for (int k = 0; k < 20; ++k) {
-      hipLaunchKernelGGL((k_cheb_first<double>), dim3(S.grid), dim3(256), 0, S.s, S.z, S.d64, S.r, S.dinv, S.n, 1.0);
-      DG_TRY(S.dot(S.r, S.z, sc + RZ0));
-      const double rz = S.host(sc + RZ0);
-      if (!(rz > 0) || !std::isfinite(rz)) break;
-      if (k == 0) {
-        hipLaunchKernelGGL((k_copy<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n);
-      } else {
-        be.push_back(rz / rz_old);
-        // p = z + (rz / rz_old) p with both scalars on the device
-        hipLaunchKernelGGL((k_update_p<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n, sc + RZ0,
-                           (const double*)nullptr, sc + RZ1);
-      }
-      DG_TRY(S.A64(S.p, S.q));
-      DG_TRY(S.dot(S.p, S.q, sc + PQ));
-      const double pq = S.host(sc + PQ);
-      if (!(pq > 0)) break;
-      al.push_back(rz / pq);
-      hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, S.t64, S.r, S.p, S.q,
-                         S.n, sc + RZ0, sc + PQ, S.part);
-      hipLaunchKernelGGL((k_copy<double>), dim3(1), dim3(1), 0, S.s, sc + RZ1, sc + RZ0, (int64_t)1);
-      rz_old = rz;
-    }
-    const int kk = (int)al.size();
-    if (kk < 1) return set_error(DG_ERR_NONFINITE, "eigenvalue estimate failed");
-    std::vector<double> diag(kk), off(kk > 1 ? kk - 1 : 0);
-    for (int j = 0; j < kk; ++j) {
-      diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
-      if (j + 1 < kk) off[j] = std::sqrt(be[j]) / al[j];
-    }
-    mm->lam_max = tridiag_max_eig(diag, off);
+    DG_TRY(S.lanczos(0, &mm->lam_max));
     S.applies64 = 0;
+  }
+  if (use_mg) {
+    mm->mg[0].lam = mm->lam_max;
+    for (int l = 1; l < S.nlev; ++l) {
+      const unsigned g = Solver::grid_of(S.lv[l].n);
+      hipLaunchKernelGGL((k_recip<double>), dim3(g), dim3(256), 0, S.s, S.lv[l].dinv64, m->mg[l].diag, S.lv[l].n);
+      hipLaunchKernelGGL((k_recip<float>), dim3(g), dim3(256), 0, S.s, S.lv[l].dinv32, m->mg[l].diag, S.lv[l].n);
+      const bool need = l < S.nlev - 1 || !m->coarse_inv;
+      if (need && !(mm->mg[l].lam > 0)) DG_TRY(S.lanczos(l, &mm->mg[l].lam));
+    }
   }
   const double lmax = 1.1 * mm->lam_max, lmin = mm->lam_max / 30.0;
   const int deg = sp->cheb_degree;
@@ -401,6 +569,14 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   };
   // preconditioner z = M^{-1} r
   auto precond = [&](double* zz) -> int {
+    if (use_mg && !sp->mixed) return S.vcycle<double>(0, zz, S.r, S.q, S.d64, S.t64, deg);
+    if (use_mg) {
+      hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR);
+      int e = S.vcycle<float>(0, S.x32, S.r32, S.rr32, S.d32, S.t32, deg);
+      if (e) return e;
+      hipLaunchKernelGGL(k_from_f32, dim3(S.grid), dim3(256), 0, S.s, zz, S.x32, S.n, sc + RR);
+      return check_hip(hipGetLastError(), "preconditioner");
+    }
     if (!sp->mixed) return S.cheb<double>(zz, S.r, S.d64, S.t64, S.dinv, deg, lmin, lmax);
     // normalised FP32 copy of r (||r||^2 is in sc[RR])
     hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR);

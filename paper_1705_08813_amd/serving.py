@@ -126,7 +126,7 @@ class Server:
         self.slots = int(slots)
         self.workers = int(workers)
         self.applies = int(applies)
-        kw = dict(rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5)
+        kw = dict(rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5, multigrid=True)
         kw.update(solve_kw or {})
         self.solve_kw = kw
         self.keep = keep_results
@@ -137,7 +137,8 @@ class Server:
     def _sp(self):
         k = self.solve_kw
         return _lib.SolveParams(rtol=k["rtol"], max_outer=k["max_outer"], max_inner=k["max_inner"],
-                                cheb_degree=k["cheb_degree"], inner_rtol=0.0, mixed=int(k["mixed"]))
+                                cheb_degree=k["cheb_degree"], inner_rtol=0.0, mixed=int(k["mixed"]),
+                                multigrid=int(k["multigrid"]))
 
     # -- worker jobs (run on pool threads, each on its own stream) ---------
     def _stream(self):
