@@ -53,7 +53,7 @@ def test_solve_large_mixed_and_f64():
     bt = torch.tensor(b, device="cuda")
     for mixed in (True, False):
         _log(f"[gpu] solve large mixed={mixed}")
-        x, st = mesh.solve_poisson(bt, sp=mesh.solve_params(mixed=mixed))
+        x, st = mesh.solve_poisson(bt, sp=mesh.solve_params(mixed=mixed, multigrid=False))
         _log(f"[gpu]   its={st.outer_its} f64={st.op_applies_f64} f32={st.op_applies_f32} "
              f"rel={st.rel_resid:.2e} t={st.seconds:.3f}s")
         assert st.rel_resid <= 1e-10
@@ -70,3 +70,51 @@ def test_solve_zero_rhs_and_iteration_cap():
     with pytest.raises(DgError) as ei:
         mesh.solve_poisson(b, sp=mesh.solve_params(max_outer=2))
     assert ei.value.code == -5
+
+
+MG_CASES = {
+    # every direction coarsens (levels down to a 1x2x1 mesh)
+    "k3_stretched": MeshConfig(nx=8, ny=8, nz=4, gamma=1.8, k_p=3, nq_p=4, k_u=4, nq_u=7),
+    # odd nx: x is never coarsened (identity transfer along x)
+    "k2_odd_x": MeshConfig(nx=3, ny=8, nz=4, gamma=1.2, k_p=2, nq_p=3, k_u=3, nq_u=5),
+    # periodic in y as well: y coarsens down to one cell
+    "k1_periodic": MeshConfig(nx=8, ny=4, nz=8, k_p=1, nq_p=2, k_u=2, nq_u=4, fully_periodic=1),
+    # degree 4 pressure, coarsest level larger than the dense threshold target
+    "k4_walls": MeshConfig(nx=4, ny=4, nz=4, gamma=1.0, k_p=4, nq_p=5, k_u=5, nq_u=8),
+    # two levels, coarsest (3x3x3, 1728 unknowns) too large for the dense inverse:
+    # smoothed with the long Chebyshev polynomial instead
+    "k3_cheb_coarse": MeshConfig(nx=6, ny=6, nz=6, gamma=1.0, k_p=3, nq_p=4, k_u=4, nq_u=7),
+}
+
+
+@pytest.mark.parametrize("name", list(MG_CASES))
+@pytest.mark.parametrize("mixed", [True, False])
+def test_multigrid_solve_matches_oracle(name, mixed):
+    cfg = MG_CASES[name]
+    _log(f"[gpu] multigrid solve case={name} mixed={mixed}")
+    b = np.random.default_rng(11).uniform(-1, 1, cfg.n_p)
+    mesh = Mesh(cfg)
+    bt = torch.tensor(b, device="cuda")
+    x, st = mesh.solve_poisson(bt, sp=mesh.solve_params(mixed=mixed, multigrid=True))
+    _log(f"[gpu]   its={st.outer_its} rel={st.rel_resid:.2e}")
+    assert st.rel_resid <= 1e-10
+    assert _oracle_relres(cfg, x.cpu().numpy(), b) <= 1.05e-10
+    # the polynomial-only preconditioner reaches the same solution, with more iterations
+    x2, st2 = mesh.solve_poisson(bt, sp=mesh.solve_params(mixed=mixed, multigrid=False))
+    _log(f"[gpu]   chebyshev-only its={st2.outer_its}")
+    assert st.outer_its <= st2.outer_its
+    xa, xb = x.cpu().numpy(), x2.cpu().numpy()
+    assert np.linalg.norm(xa - xb) <= 1e-7 * np.linalg.norm(xb)
+
+
+def test_multigrid_large_iteration_count():
+    # 64x32x32, k_p = 3, tanh 1.8: the V-cycle keeps the outer iteration count
+    # in the range the paper reports for its multigrid-preconditioned solver
+    wl = PRESETS["precision"]
+    cfg = wl.mesh
+    b = np.random.default_rng(wl.seed).uniform(-1, 1, cfg.n_p)
+    mesh = Mesh(cfg)
+    x, st = mesh.solve_poisson(torch.tensor(b, device="cuda"), sp=mesh.solve_params(mixed=True, multigrid=True))
+    _log(f"[gpu] large multigrid its={st.outer_its} f32 applies={st.op_applies_f32} rel={st.rel_resid:.2e}")
+    assert st.rel_resid <= 1e-10 and st.outer_its <= 30
+    assert _oracle_relres(cfg, x.cpu().numpy(), b) <= 1.05e-10
