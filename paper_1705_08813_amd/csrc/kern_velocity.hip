@@ -933,9 +933,14 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
 }
 
 template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
-__global__ __launch_bounds__(256, 3) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
+__global__ __launch_bounds__(256, CURVED ? 2 : 3) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
                                                   int layer_lo, int nlayers) {
-  vel_cell<T, NP, NQ, NQY, ENR, CURVED>(M, u, r, blockIdx.x, layer_lo, nlayers);
+  // contiguous cell ranges per XCD (workgroups are dealt round-robin over
+  // the 8 XCDs), so neighbouring cells share an L2
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = bid & 7, m8 = bid >> 3;
+  const int blk = xcd * q8 + (xcd < r8 ? xcd : r8) + m8;
+  vel_cell<T, NP, NQ, NQY, ENR, CURVED>(M, u, r, blk, layer_lo, nlayers);
 }
 
 }  // namespace
@@ -955,7 +960,7 @@ namespace {
 // item i.  Each cell runs exactly the code of the single-mesh kernel, so the
 // results are bit-for-bit the same.
 template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
-__global__ __launch_bounds__(256, 3) void vel_kernel_batched(const VelBatchItem* __restrict__ items,
+__global__ __launch_bounds__(256, CURVED ? 2 : 3) void vel_kernel_batched(const VelBatchItem* __restrict__ items,
                                                           const int64_t* __restrict__ prefix, int nitems) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = nitems;
