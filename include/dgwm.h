@@ -199,10 +199,17 @@ int64_t dg_solve_workspace_bytes_for(const dg_mesh_params* params, const dg_solv
  * Outer loop: flexible preconditioned CG in FP64 (residuals, norms and dot
  * products always FP64, deterministic fixed-order reductions, true residual
  * recomputed periodically and before convergence is accepted).
- * Preconditioner: Chebyshev polynomial of degree cheb_degree in D^{-1} A on
- * [lmax/30, 1.1 lmax] (lmax from 20 Lanczos steps, cached in the mesh); with
- * mixed = 1 its operator applications run in FP32 on the normalised
- * residual, optionally wrapped in max_inner FP32 CG iterations.
+ * Preconditioner (the paper's solver is multigrid-preconditioned CG, Sec. 4.4):
+ *   multigrid = 1: one V-cycle over the mesh's nested h-levels (cell pairs
+ *     merged along every direction with an even count), smoothing by the
+ *     degree-cheb_degree Chebyshev polynomial in D^{-1} A_l on
+ *     [lmax_l/20, 1.1 lmax_l], transfers by the exact embedding of the coarse
+ *     DG space and its transpose, the coarsest level by a dense
+ *     pseudo-inverse; max_inner is ignored;
+ *   multigrid = 0: the Chebyshev polynomial on [lmax/30, 1.1 lmax] alone,
+ *     optionally wrapped in max_inner FP32 CG iterations.
+ * lmax of each level comes from 20 Lanczos steps and is cached in the mesh.
+ * With mixed = 1 the preconditioner runs in FP32 on the normalised residual.
  * Reads back one scalar per outer iteration and returns when converged.
  *   b, x: device double vectors; workspace: dg_solve_workspace_bytes().
  *   Errors: DG_ERR_NOT_CONVERGED (stats filled) after max_outer iterations,

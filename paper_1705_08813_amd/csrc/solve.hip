@@ -5,12 +5,15 @@
 // norms, dot products and the solution always FP64), with the true residual
 // b - A x recomputed (residual replacement) every few iterations and before
 // accepting convergence.  Preconditioner:
-//   mixed = 0: Chebyshev polynomial of degree m in D^{-1} A, FP64;
-//   mixed = 1: the same polynomial with FP32 operator applications, or, with
-//              max_inner > 0, that many FP32 preconditioned CG iterations on
-//              the normalised residual, accumulated in FP64 dot products.
-// The Chebyshev interval is [lmax/30, 1.1 lmax], lmax from 20 Lanczos steps
-// (Jacobi-preconditioned CG coefficients) cached in the mesh handle.
+//   multigrid: one V-cycle over the mesh's nested levels (the paper's solver
+//              is multigrid-preconditioned, Sec. 4.4), Chebyshev-Jacobi
+//              smoothing, restriction/prolongation of kern_mg.hip, dense
+//              pseudo-inverse on the coarsest level;
+//   otherwise: Chebyshev polynomial of degree m in D^{-1} A on
+//              [lmax/30, 1.1 lmax], optionally wrapped in FP32 CG iterations.
+// mixed = 1 runs the preconditioner in FP32 on the normalised residual.
+// lmax of each level from 20 Lanczos steps (Jacobi-preconditioned CG
+// coefficients kept on the device), cached in the mesh handle.
 // Every reduction is a fixed-grid two-stage FP64 sum: deterministic.
 // The null space (constants) is handled by projecting b and x to zero mean.
 #include <algorithm>
