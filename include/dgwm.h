@@ -76,7 +76,16 @@ typedef struct {
   double ip_factor_u, ip_factor_p; /* multipliers of the (k+1)^2 |F|/|Omega| penalty      */
   double wall_ip_mult;    /* extra penalty factor on no-slip faces (paper: 10)            */
   double theta;           /* adjoint-term sign of the viscous form (+1 symmetric IP)      */
+  int32_t psi_kind;       /* enrichment function: DG_PSI_SPALDING or DG_PSI_VANDRIEST     */
+  double A_plus;          /* van Driest damping constant A+ (paper: 26)                   */
 } dg_mesh_params;
+
+/* Wall laws for psi = U(y+) (paper Sec. 3.2): Spalding's implicit law with
+ * (kappa, B), or van Driest's law (eq. psi) U = int_0^{y+} 2 / (1 + sqrt(1 +
+ * (2 kappa s (1 - exp(-s/A+)))^2)) ds, evaluated as in the paper's Appendix A:
+ * the integral is tabulated at support points y+_i and the remaining slice
+ * [y+_i, y+] is integrated with a 9-point Gauss rule. */
+enum { DG_PSI_SPALDING = 0, DG_PSI_VANDRIEST = 1 };
 
 /* ---------------------------------------------------------------- mesh --- */
 

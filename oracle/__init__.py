@@ -35,6 +35,7 @@ class OrcParams(ctypes.Structure):
         ("nu", ctypes.c_double), ("kappa", ctypes.c_double), ("B", ctypes.c_double),
         ("ip_factor_u", ctypes.c_double), ("ip_factor_p", ctypes.c_double),
         ("wall_ip_mult", ctypes.c_double), ("theta", ctypes.c_double),
+        ("psi_kind", ctypes.c_int32), ("A_plus", ctypes.c_double),
     ]
 
 
@@ -54,6 +55,7 @@ def lib():
         L.orc_lagrange.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D, _D]
         L.orc_lagrange.restype = None
         L.orc_spalding.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.orc_vandriest.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
         L.orc_vertex_eta.argtypes = [P, _D]
         L.orc_vertex_eta.restype = None
         L.orc_num_dofs.argtypes = [P, ctypes.c_int]
@@ -121,6 +123,15 @@ def spalding(yplus, kappa=0.41, B=5.17):
     U = ctypes.c_double()
     dU = ctypes.c_double()
     if lib().orc_spalding(float(yplus), kappa, B, ctypes.byref(U), ctypes.byref(dU)):
+        raise ValueError("bad y+")
+    return U.value, dU.value
+
+
+def vandriest(yplus, kappa=0.41, A_plus=26.0):
+    """van Driest's law U(y+) (Sec. 3.2, eq. psi) and dU/dy+ by composite Gauss."""
+    U = ctypes.c_double()
+    dU = ctypes.c_double()
+    if lib().orc_vandriest(float(yplus), kappa, A_plus, ctypes.byref(U), ctypes.byref(dU)):
         raise ValueError("bad y+")
     return U.value, dU.value
 

@@ -54,6 +54,8 @@ typedef struct {
   int32_t enrich_lower, enrich_upper, fully_periodic;
   double nu, kappa, B;
   double ip_factor_u, ip_factor_p, wall_ip_mult, theta;
+  int32_t psi_kind; /* 0: Spalding's law, 1: van Driest's law (Sec. 3.2, eq. psi) */
+  double A_plus;    /* van Driest damping constant A+ */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -177,6 +179,34 @@ int orc_spalding(double yp, double kappa, double B, double *U_out, double *dU_ou
   }
   *U_out = U;
   *dU_out = 1.0 / spalding_df(U, kappa, B);
+  return 0;
+}
+
+/* van Driest's law (Sec. 3.2, eq. psi): U(y+) = int_0^{y+} f, with
+ * f(s) = 2 / (1 + sqrt(1 + (2 kappa s (1 - exp(-s/A+)))^2)), dU/dy+ = f(y+).
+ * Composite Gauss-Legendre from 0 (no tabulation): 12-point panels of width 1
+ * up to s = 64, then panels growing by 10 % per step; the integrand is
+ * analytic, so each panel is exact to rounding. */
+static double vandriest_f(double s, double kappa, double Ap) {
+  double m = 2.0 * kappa * s * (1.0 - exp(-s / Ap));
+  return 2.0 / (1.0 + sqrt(1.0 + m * m));
+}
+
+int orc_vandriest(double yp, double kappa, double Ap, double *U_out, double *dU_out) {
+  if (!(yp >= 0.0) || !(kappa > 0.0) || !(Ap > 0.0)) return -1;
+  double x[ORC_MAXN], w[ORC_MAXN];
+  orc_gauss(12, x, w);
+  double U = 0.0, a = 0.0;
+  while (a < yp) {
+    double width = a < 64.0 ? 1.0 : 0.1 * a;
+    double b = a + width < yp ? a + width : yp;
+    double sum = 0.0;
+    for (int q = 0; q < 12; ++q) sum += w[q] * vandriest_f(a + (b - a) * x[q], kappa, Ap);
+    U += (b - a) * sum;
+    a = b;
+  }
+  *U_out = U;
+  *dU_out = vandriest_f(yp, kappa, Ap);
   return 0;
 }
 
@@ -359,7 +389,7 @@ typedef struct { double psi, g[3]; } psi_pt;
  * y_h: trilinear (m = 1) interpolation of the vertex wall distances.
  * tau_w: value of the wall-face Gauss column nearest to (xi_x, xi_z) in the
  * cell's velocity rule; treated as locally constant (zero gradient).
- * y+ = y_h sqrt(tau_w)/nu (rho = 1), psi = U_Spalding(y+),
+ * y+ = y_h sqrt(tau_w)/nu (rho = 1), psi = U(y+) of the chosen law,
  * grad psi = U'(y+) sqrt(tau_w)/nu grad y_h. */
 static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double Ji[3][3], psi_pt *out) {
   int ex, ey, ez;
@@ -392,7 +422,10 @@ static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double J
   int64_t ti = (((int64_t)w * C->P.nz + ez) * C->P.nx + ex) * nq * nq + (int64_t)qz * nq + qx;
   double st = sqrt(C->tau[ti]) / C->P.nu;
   double U, dU;
-  orc_spalding(yh * st, C->P.kappa, C->P.B, &U, &dU);
+  if (C->P.psi_kind == 1)
+    orc_vandriest(yh * st, C->P.kappa, C->P.A_plus, &U, &dU);
+  else
+    orc_spalding(yh * st, C->P.kappa, C->P.B, &U, &dU);
   out->psi = U;
   for (int d = 0; d < 3; ++d) out->g[d] = dU * st * gyh[d];
 }

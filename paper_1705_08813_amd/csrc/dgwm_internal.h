@@ -101,7 +101,7 @@ namespace dgwm {
 // vertices of a coarse level are every second vertex of the finer one, so
 // the levels are nested and the coarse space is a subspace of the fine one.
 constexpr int kMaxLevels = 12;
-constexpr int kMaxCoarseDofs = 512;   // largest coarsest level solved with the dense inverse
+constexpr int kMaxCoarseDofs = 1024;  // largest coarsest level solved with the dense inverse
 constexpr int kCoarseTarget = 128;    // coarsen while a level has more unknowns than this
 struct MgLevel {
   int nx = 0, ny = 0, nz = 0;
@@ -172,6 +172,13 @@ int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipSt
 int launch_poisson_level(const dg_mesh* m, int level, dg_prec prec, const void* p, void* y, hipStream_t s,
                          int nvec = 1, int64_t vstride = 0);
 int launch_poisson_diag_level(const dg_mesh* m, int level, hipStream_t s);
+// fused solver steps on level l: r = b - A x, and one Chebyshev step
+// v = c1 d + c2 dinv (b - A z), d = v, zout = z + v (zout != z)
+template <typename T>
+int launch_poisson_resid(const dg_mesh* m, int level, const T* x, const T* b, T* r, hipStream_t s);
+template <typename T>
+int launch_poisson_cheb(const dg_mesh* m, int level, const T* z, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
+                        hipStream_t s);
 // multigrid transfers between level l (fine) and l + 1 (coarse)
 int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s);
 int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, void* xf, hipStream_t s);

@@ -99,9 +99,11 @@ __device__ __forceinline__ void sweep(const T* __restrict__ in, int IS, T* __res
 // The workgroup size NT is a compile-time constant, so a line count below NT
 // gives each thread at most one line and the table literals stay local to
 // straight-line code.
+// tofs rotates the thread-to-line assignment, so that independent sweeps of
+// one phase fill the threads a previous sweep left idle.
 template <int DIR, int I0, int I1, int I2, int MO, bool TR, bool ADD, typename MAT, int NT = 256, typename T>
 __device__ __forceinline__ void sweep_c(const T* __restrict__ in, int IS, T* __restrict__ out, int OS, T scale,
-                                        int ncomp) {
+                                        int ncomp, int tofs = 0) {
   constexpr int NI = DIR == 0 ? I0 : (DIR == 1 ? I1 : I2);
   constexpr int O0 = DIR == 0 ? MO : I0;
   constexpr int O1 = DIR == 1 ? MO : I1;
@@ -110,7 +112,8 @@ __device__ __forceinline__ void sweep_c(const T* __restrict__ in, int IS, T* __r
   constexpr int NPEN = P0 * P1;
   constexpr int SIN = DIR == 0 ? 1 : (DIR == 1 ? I0 : I0 * I1);
   constexpr int SOUT = DIR == 0 ? 1 : (DIR == 1 ? O0 : O0 * O1);
-  for (int t = threadIdx.x; t < NPEN * ncomp; t += NT) {
+  const int t0 = (int)threadIdx.x >= tofs ? (int)threadIdx.x - tofs : (int)threadIdx.x + NT - tofs;
+  for (int t = t0; t < NPEN * ncomp; t += NT) {
     const int c = t / NPEN, p = t - c * NPEN;
     const int a = p % P0, b = p / P0;
     int ib, ob;
@@ -139,6 +142,38 @@ __device__ __forceinline__ void sweep_c(const T* __restrict__ in, int IS, T* __r
       else
         dst[m * SOUT] = scale * s;
     }
+  }
+}
+
+// In-place square sweep (MO = NI): every thread reads its whole line into
+// registers before writing it back, and lines are disjoint, so input and
+// output may be the same array (no __restrict__ here on purpose).
+template <int DIR, int I0, int I1, int I2, bool TR, typename MAT, int NT = 256, typename T>
+__device__ __forceinline__ void sweep_c_inplace(T* a, int IS, T scale, int ncomp, int tofs = 0) {
+  constexpr int NI = DIR == 0 ? I0 : (DIR == 1 ? I1 : I2);
+  constexpr int P0 = DIR == 0 ? I1 : I0;
+  constexpr int P1 = DIR == 2 ? I1 : I2;
+  constexpr int NPEN = P0 * P1;
+  constexpr int SIN = DIR == 0 ? 1 : (DIR == 1 ? I0 : I0 * I1);
+  const int t0 = (int)threadIdx.x >= tofs ? (int)threadIdx.x - tofs : (int)threadIdx.x + NT - tofs;
+  for (int t = t0; t < NPEN * ncomp; t += NT) {
+    const int c = t / NPEN, p = t - c * NPEN;
+    const int aa = p % P0, b = p / P0;
+    const int ib = DIR == 0 ? I0 * (aa + I1 * b) : (DIR == 1 ? aa + I0 * I1 * b : aa + I0 * b);
+    T* line = a + c * IS + ib;
+    T v[NI];
+#pragma unroll
+    for (int n = 0; n < NI; ++n) v[n] = line[n * SIN];
+    T w[NI];
+#pragma unroll
+    for (int m = 0; m < NI; ++m) {
+      T s = 0;
+#pragma unroll
+      for (int n = 0; n < NI; ++n) s += T(TR ? MAT::at(n, m) : MAT::at(m, n)) * v[n];
+      w[m] = scale * s;
+    }
+#pragma unroll
+    for (int m = 0; m < NI; ++m) line[m * SIN] = w[m];
   }
 }
 

@@ -10,6 +10,7 @@
 //                            child 0: xi_c = r xi_f, child 1: r + (1 - r) xi_f.
 // Restriction of residuals (dual vectors) is the transpose.  One workgroup
 // per coarse cell; every fine entry has a single writer.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -21,12 +22,27 @@ namespace {
 
 // N_i(x) of the NP-node Lobatto basis
 template <int NP>
+struct LobattoDen {  // 1 / prod_{j != i} (x_i - x_j)
+  double inv[NP];
+  constexpr LobattoDen() : inv{} {
+    for (int i = 0; i < NP; ++i) {
+      double d = 1.0;
+      for (int j = 0; j < NP; ++j)
+        if (j != i) d *= ct::lobatto<NP>.x[i] - ct::lobatto<NP>.x[j];
+      inv[i] = 1.0 / d;
+    }
+  }
+};
+template <int NP>
+inline constexpr LobattoDen<NP> lobatto_den{};
+
+template <int NP>
 __device__ __forceinline__ double lobatto_basis(int i, double x) {
   constexpr auto& L = ct::lobatto<NP>;
-  double v = 1.0;
+  double v = lobatto_den<NP>.inv[i];
 #pragma unroll
   for (int j = 0; j < NP; ++j)
-    if (j != i) v *= (x - L.x[j]) / (L.x[i] - L.x[j]);
+    if (j != i) v *= x - L.x[j];
   return v;
 }
 
@@ -171,15 +187,27 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* _
   }
 }
 
-// x = B b for a dense symmetric B (n x n), one thread per entry of x
+// x = B b for a dense symmetric B (n x n, n <= kMaxCoarseDofs): b staged in
+// LDS, one thread per entry of x, four independent partial sums so that the
+// column loads of B stay in flight.
 template <typename T>
-__global__ __launch_bounds__(256) void dense_apply_kernel(int64_t n, const T* __restrict__ B, const T* __restrict__ b,
+__global__ __launch_bounds__(256) void dense_apply_kernel(int n, const T* __restrict__ B, const T* __restrict__ b,
                                                           T* __restrict__ x) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  __shared__ T sb[kMaxCoarseDofs];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sb[j] = b[j];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  T s = 0;
-  for (int64_t j = 0; j < n; ++j) s += B[j * n + i] * b[j];
-  x[i] = s;
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    s0 += B[(int64_t)j * n + i] * sb[j];
+    s1 += B[(int64_t)(j + 1) * n + i] * sb[j + 1];
+    s2 += B[(int64_t)(j + 2) * n + i] * sb[j + 2];
+    s3 += B[(int64_t)(j + 3) * n + i] * sb[j + 3];
+  }
+  for (; j < n; ++j) s0 += B[(int64_t)j * n + i] * sb[j];
+  x[i] = (s0 + s1) + (s2 + s3);
 }
 
 // columns of the n x n identity, one vector of n entries per column
@@ -251,12 +279,13 @@ int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc,
 }
 
 int launch_dense_apply(int64_t n, dg_prec prec, const void* B, const void* b, void* x, hipStream_t s) {
+  if (n > kMaxCoarseDofs) return set_error(DG_ERR_ARG, "dense coarse solve larger than its limit");
   const unsigned nb = (unsigned)((n + 255) / 256);
   if (prec == DG_F64)
-    hipLaunchKernelGGL((dense_apply_kernel<double>), dim3(nb), dim3(256), 0, s, n, static_cast<const double*>(B),
-                       static_cast<const double*>(b), static_cast<double*>(x));
+    hipLaunchKernelGGL((dense_apply_kernel<double>), dim3(nb), dim3(256), 0, s, (int)n,
+                       static_cast<const double*>(B), static_cast<const double*>(b), static_cast<double*>(x));
   else
-    hipLaunchKernelGGL((dense_apply_kernel<float>), dim3(nb), dim3(256), 0, s, n, static_cast<const float*>(B),
+    hipLaunchKernelGGL((dense_apply_kernel<float>), dim3(nb), dim3(256), 0, s, (int)n, static_cast<const float*>(B),
                        static_cast<const float*>(b), static_cast<float*>(x));
   return check_hip(hipGetLastError(), "dense apply launch");
 }
@@ -276,7 +305,10 @@ int mg_plan(const dg_mesh_params& P, MgLevel* lv) {
   lv[0].hz = P.Lz / P.nz;
   while (n < kMaxLevels) {
     const MgLevel& f = lv[n - 1];
-    if (f.n <= kCoarseTarget) break;  // small enough for the dense coarse solve
+    // small enough for the dense coarse solve: 128 unknowns, or up to
+    // 1024 on large meshes (fewer latency-bound tiny levels per V-cycle)
+    const int64_t target = std::max<int64_t>(kCoarseTarget, std::min<int64_t>(1024, lv[0].n / 4096));
+    if (f.n <= target) break;
     const int cx = (f.nx % 2 == 0) ? 1 : 0;
     const int cy = (f.ny % 2 == 0 && (P.fully_periodic ? f.ny >= 2 : f.ny >= 4)) ? 1 : 0;
     const int cz = (f.nz % 2 == 0) ? 1 : 0;
@@ -344,35 +376,45 @@ int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hi
       A[i * n + j] = A[j * n + i] = v;
     }
   for (int64_t t = 0; t < n * n; ++t) A[t] += alpha;
-  // Cholesky A = L L^T (lower, in place), then B = L^{-T} L^{-1}
+  // Cholesky A = L L^T (lower, in place), W = L^{-1} row by row, then
+  // B = W^T W accumulated row by row (all inner loops contiguous)
   for (int64_t j = 0; j < n; ++j) {
     double d = A[j * n + j];
     for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
     if (!(d > 0)) return set_error(DG_ERR_NONFINITE, "coarsest operator is not positive definite");
     d = std::sqrt(d);
     A[j * n + j] = d;
+    const double* Lj = &A[j * n];
     for (int64_t i = j + 1; i < n; ++i) {
-      double v = A[i * n + j];
-      for (int64_t k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+      const double* Li = &A[i * n];
+      double v = Li[j];
+      for (int64_t k = 0; k < j; ++k) v -= Li[k] * Lj[k];
       A[i * n + j] = v / d;
     }
   }
-  std::vector<double> Li(n * n, 0.0);  // L^{-1}, lower
-  for (int64_t j = 0; j < n; ++j) {
-    Li[j * n + j] = 1.0 / A[j * n + j];
-    for (int64_t i = j + 1; i < n; ++i) {
-      double v = 0;
-      for (int64_t k = j; k < i; ++k) v -= A[i * n + k] * Li[k * n + j];
-      Li[i * n + j] = v / A[i * n + i];
+  std::vector<double> W(n * n, 0.0);  // L^{-1}, lower
+  for (int64_t i = 0; i < n; ++i) {
+    double* Wi = &W[i * n];
+    Wi[i] = 1.0;
+    for (int64_t k = 0; k < i; ++k) {
+      const double lik = A[i * n + k];
+      const double* Wk = &W[k * n];
+      for (int64_t j = 0; j <= k; ++j) Wi[j] -= lik * Wk[j];
     }
+    const double inv = 1.0 / A[i * n + i];
+    for (int64_t j = 0; j <= i; ++j) Wi[j] *= inv;
   }
   std::vector<double> B(n * n, 0.0);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t j = 0; j <= i; ++j) {
-      double v = 0;
-      for (int64_t k = i; k < n; ++k) v += Li[k * n + i] * Li[k * n + j];
-      B[i * n + j] = B[j * n + i] = v;
+  for (int64_t k = 0; k < n; ++k) {
+    const double* Wk = &W[k * n];
+    for (int64_t i = 0; i <= k; ++i) {
+      const double w = Wk[i];
+      double* Bi = &B[i * n];
+      for (int64_t j = 0; j <= i; ++j) Bi[j] += w * Wk[j];
     }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) B[j * n + i] = B[i * n + j];
   rc = check_hip(hipMemcpyAsync(m->coarse_inv, B.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s),
                  "coarse inverse");
   if (!rc) hipLaunchKernelGGL(to_f32_kernel, dim3(256), dim3(256), 0, s, m->coarse_inv32, m->coarse_inv, n * n);

@@ -28,6 +28,22 @@ __device__ __forceinline__ int64_t poi_nb(const MeshDev& M, int ex, int ey, int 
   return x + (int64_t)M.nx * (yy + (int64_t)M.ny * z);
 }
 
+// What the kernel does with y = A p at each output entry (solver fusion):
+//   kPlain: y = A p
+//   kResid: r = b - A p
+//   kCheb:  v = c1 d + c2 dinv (b - A p), d = v, zout = p + v (one step of
+//           the Chebyshev recurrence; zout must not alias p; c1 = 0 ignores d)
+enum PoiEpiKind { kPlain = 0, kResid = 1, kCheb = 2 };
+template <typename T>
+struct PoiEpi {
+  int kind;
+  const T* b;
+  const T* dinv;
+  T* d;
+  T* zout;
+  T c1, c2;
+};
+
 // Cells per workgroup: one thread per pencil (line of NP nodes), so a cell
 // uses NP^2 threads and a 256-thread workgroup holds 256 / NP^2 cells.
 template <int NP>
@@ -63,7 +79,8 @@ __device__ __forceinline__ constexpr int pencil_stride(int D) {
 // one writer).
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y,
-                                                      int64_t ncell, int nblocks, int64_t vstride) {
+                                                      int64_t ncell, int nblocks, int64_t vstride,
+                                                      const PoiEpi<T> E) {
   using BL = PoiBlk<NP>;
   // blockIdx.y selects one of several vectors stored vstride apart
   p += blockIdx.y * vstride;
@@ -249,13 +266,22 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
     T u[NP];
 #pragma unroll
     for (int l = 0; l < NP; ++l) u[l] = sZ[bx + l];
-    T* ye = y + e * NP3 + bx;
+    const int64_t o = e * NP3 + bx;
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
       T s = sX[bx + l];
 #pragma unroll
       for (int m = 0; m < NP; ++m) s += Mm[l * NP + m] * u[m];
-      ye[l] = s;
+      if (E.kind == kPlain) {
+        y[o + l] = s;
+      } else if (E.kind == kResid) {
+        y[o + l] = E.b[o + l] - s;
+      } else {
+        T v = E.c2 * E.dinv[o + l] * (E.b[o + l] - s);
+        if (E.c1 != T(0)) v += E.c1 * E.d[o + l];
+        E.d[o + l] = v;
+        E.zout[o + l] = px[l] + v;
+      }
     }
   }
 }
@@ -360,25 +386,53 @@ bool poisson_supported(int np, int nq) {
 
 const char* poisson_combos() { return "poisson (k+1, nq_p): (2,2) (3,3) (4,4) (5,5) (6,6)"; }
 
-int launch_poisson_level(const dg_mesh* m, int l, dg_prec prec, const void* p, void* y, hipStream_t s, int nvec,
-                         int64_t vstride) {
+template <typename T>
+static int launch_poisson_t(const dg_mesh* m, int l, const T* p, T* y, hipStream_t s, int nvec, int64_t vstride,
+                     const PoiEpi<T>& E) {
   const MeshDev M = make_meshdev_p(m, l);
   const int64_t ncell = l > 0 ? m->mg[l].ncell : m->ncell;
 #define X(a, b)                                                                                           \
   if (m->np_p == a && m->P.nq_p == b) {                                                                   \
     const int nb = (int)((ncell + PoiBlk<a>::CB - 1) / PoiBlk<a>::CB);                                    \
-    if (prec == DG_F64)                                                                                   \
-      hipLaunchKernelGGL((poisson_kernel<double, a>), dim3(nb, nvec), dim3(256), 0, s, M,                 \
-                         static_cast<const double*>(p), static_cast<double*>(y), ncell, nb, vstride);     \
-    else                                                                                                  \
-      hipLaunchKernelGGL((poisson_kernel<float, a>), dim3(nb, nvec), dim3(256), 0, s, M,                  \
-                         static_cast<const float*>(p), static_cast<float*>(y), ncell, nb, vstride);       \
+    hipLaunchKernelGGL((poisson_kernel<T, a>), dim3(nb, nvec), dim3(256), 0, s, M, p, y, ncell, nb,       \
+                       vstride, E);                                                                       \
     return check_hip(hipGetLastError(), "poisson kernel launch");                                         \
   }
   DG_POI_COMBOS(X)
 #undef X
   return set_error(DG_ERR_UNSUPPORTED, "poisson degree/quadrature combination not compiled");
 }
+
+int launch_poisson_level(const dg_mesh* m, int l, dg_prec prec, const void* p, void* y, hipStream_t s, int nvec,
+                         int64_t vstride) {
+  if (prec == DG_F64) {
+    const PoiEpi<double> E{kPlain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0};
+    return launch_poisson_t<double>(m, l, static_cast<const double*>(p), static_cast<double*>(y), s, nvec, vstride,
+                                    E);
+  }
+  const PoiEpi<float> E{kPlain, nullptr, nullptr, nullptr, nullptr, 0.0f, 0.0f};
+  return launch_poisson_t<float>(m, l, static_cast<const float*>(p), static_cast<float*>(y), s, nvec, vstride, E);
+}
+
+template <typename T>
+int launch_poisson_resid(const dg_mesh* m, int l, const T* x, const T* b, T* r, hipStream_t s) {
+  const PoiEpi<T> E{kResid, b, nullptr, nullptr, nullptr, T(0), T(0)};
+  return launch_poisson_t<T>(m, l, x, r, s, 1, 0, E);
+}
+
+template <typename T>
+int launch_poisson_cheb(const dg_mesh* m, int l, const T* z, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
+                        hipStream_t s) {
+  const PoiEpi<T> E{kCheb, b, dinv, d, zout, c1, c2};
+  return launch_poisson_t<T>(m, l, z, nullptr, s, 1, 0, E);
+}
+
+template int launch_poisson_resid<double>(const dg_mesh*, int, const double*, const double*, double*, hipStream_t);
+template int launch_poisson_resid<float>(const dg_mesh*, int, const float*, const float*, float*, hipStream_t);
+template int launch_poisson_cheb<double>(const dg_mesh*, int, const double*, double*, double*, const double*,
+                                         const double*, double, double, hipStream_t);
+template int launch_poisson_cheb<float>(const dg_mesh*, int, const float*, float*, float*, const float*, const float*,
+                                        float, float, hipStream_t);
 
 int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s) {
   return launch_poisson_level(m, 0, prec, p, y, s);

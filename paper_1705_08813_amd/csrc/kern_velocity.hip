@@ -820,9 +820,12 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
     __syncthreads();
   }
   // gradients by collocation through the Gauss points
-  sweep_c<0, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, ix, 3);
-  sweep_c<1, NQ, NQY, NQ, NQY, false, false, Dy>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, iy, 3);
-  sweep_c<2, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, iz, 3);
+  // (the three sweeps are independent: rotated thread assignments pack them)
+  constexpr int NLG = 3 * NPTS / NQ;   // lines per x- or z-sweep (3 components)
+  constexpr int NLY = 3 * NPTS / NQY;  // lines per y-sweep
+  sweep_c<0, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0);
+  sweep_c<1, NQ, NQY, NQ, NQY, false, false, Dy>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, iy, 3, NLG % 256);
+  sweep_c<2, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, iz, 3, (NLG + NLY) % 256);
   __syncthreads();
 
   // pointwise flux G = 2 nu eps(u) - u (x) u, times the quadrature weight
@@ -886,17 +889,42 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   }
   __syncthreads();
 
-  // integrate: W = sum_d D_d^T G_d / h_d, then transposed interpolation
-  sweep_c<0, NQ, NQY, NQ, NQ, true, false, Dx>(s_grad + 0 * NPTS, 3 * NPTS, s_val, NPTS, ix, 3);
-  __syncthreads();
-  sweep_c<1, NQ, NQY, NQ, NQY, true, true, Dy>(s_grad + 1 * NPTS, 3 * NPTS, s_val, NPTS, iy, 3);
-  __syncthreads();
-  sweep_c<2, NQ, NQY, NQ, NQ, true, true, Dx>(s_grad + 2 * NPTS, 3 * NPTS, s_val, NPTS, iz, 3);
+  // integrate: W = sum_d D_d^T G_d / h_d, then transposed interpolation.
+  // The x and y parts are formed in place (one phase); each z line then adds
+  // its own D_z^T G_z to them and applies S_z^T directly.
+  sweep_c_inplace<0, NQ, NQY, NQ, true, Dx>(s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0);
+  sweep_c_inplace<1, NQ, NQY, NQ, true, Dy>(s_grad + 1 * NPTS, 3 * NPTS, iy, 3, NLG % 256);
   __syncthreads();
   {
-    T* tB = s_grad;                       // (NQ, NQY, NP) x 3
-    T* tA = tB + 3 * NQ * NQY * NP;       // (NQ, NP, NP) x 3
-    sweep_c<2, NQ, NQY, NQ, NP, true, false, Sx>(s_val, NPTS, tB, NQ * NQY * NP, T(1), 3);
+    T* tB = s_val;                        // (NQ, NQY, NP) x 3 (u is no longer needed)
+    T* tA = s_grad;                       // (NQ, NP, NP) x 3
+    constexpr auto& tbz = ct::tab<NP, NQ>;
+    for (int t = tid; t < 3 * NQ * NQY; t += nt) {
+      const int c = t / (NQ * NQY), pq = t - c * (NQ * NQY);  // pq = qx + NQ qy
+      const T* gz = s_grad + (c * 3 + 2) * NPTS + pq;
+      const T* wx = s_grad + (c * 3 + 0) * NPTS + pq;
+      const T* wy = s_grad + (c * 3 + 1) * NPTS + pq;
+      T g[NQ], w[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) g[q] = gz[q * NQ * NQY];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) w[q] = wx[q * NQ * NQY] + wy[q * NQ * NQY];
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) {
+        T sacc = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sacc += T(tbz.D[q][m]) * g[q];
+        w[m] += iz * sacc;
+      }
+      T* o = tB + c * (NQ * NQY * NP) + pq;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        T sacc = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sacc += T(tbz.S[q][i]) * w[q];
+        o[i * NQ * NQY] = sacc;
+      }
+    }
     __syncthreads();
     sweep_c<1, NQ, NQY, NP, NP, true, false, Sy>(tB, NQ * NQY * NP, tA, NQ * NP * NP, T(1), 3);
     __syncthreads();

@@ -145,24 +145,6 @@ __global__ void k_cheb_step(T* __restrict__ z, T* __restrict__ d, const T* __res
   }
 }
 
-// Chebyshev first step from a non-zero start: d = c Dinv (b - Ax), x += d
-template <typename T>
-__global__ void k_cheb_first_res(T* __restrict__ x, T* __restrict__ d, const T* __restrict__ b,
-                                 const T* __restrict__ ax, const T* __restrict__ dinv, int64_t n, T c) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const T v = c * dinv[i] * (b[i] - ax[i]);
-    d[i] = v;
-    x[i] += v;
-  }
-}
-
-// r = b - Ax in the working precision
-template <typename T>
-__global__ void k_resid_t(T* __restrict__ r, const T* __restrict__ b, const T* __restrict__ ax, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    r[i] = b[i] - ax[i];
-}
-
 // out32 = r / sqrt(rr)
 __global__ void k_to_f32(float* __restrict__ out, const double* __restrict__ r, int64_t n,
                          const double* __restrict__ rr) {
@@ -297,7 +279,9 @@ struct Solver {
     return reinterpret_cast<const T*>(l == 0 ? dinv32 : lv[l].dinv32);
   }
   int64_t n_of(int l) const { return l == 0 ? n : lv[l].n; }
-  // z = Cheb_m(D^{-1} A_l) D^{-1} r from a zero start (m - 1 operator applications)
+  // z = Cheb_m(D^{-1} A_l) D^{-1} r from a zero start (m - 1 operator
+  // applications, each fused with its recurrence step; the iterate ping-pongs
+  // between z and t and is arranged to end in z)
   template <typename T>
   int cheb_l(int l, T* zz, const T* rr, T* dd, T* tt, int deg, double lmin, double lmax) {
     const int64_t nn = n_of(l);
@@ -305,18 +289,23 @@ struct Solver {
     const T* di = dinv_of<T>(l);
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
     double rho = 1.0 / sigma;
-    hipLaunchKernelGGL((k_cheb_first<T>), dim3(g), dim3(256), 0, s, zz, dd, rr, di, nn, (T)(1.0 / theta));
+    T* cur = ((deg - 1) % 2) ? tt : zz;
+    T* oth = cur == zz ? tt : zz;
+    hipLaunchKernelGGL((k_cheb_first<T>), dim3(g), dim3(256), 0, s, cur, dd, rr, di, nn, (T)(1.0 / theta));
     for (int k = 1; k < deg; ++k) {
-      int rc = Alev<T>(l, zz, tt);
-      if (rc) return rc;
       const double rho_new = 1.0 / (2.0 * sigma - rho);
-      hipLaunchKernelGGL((k_cheb_step<T>), dim3(g), dim3(256), 0, s, zz, dd, rr, tt, di, nn, (T)(rho_new * rho),
-                         (T)(2.0 * rho_new / delta));
+      if (l == 0) {
+        if (sizeof(T) == 8) ++applies64; else ++applies32;
+      }
+      int rc = launch_poisson_cheb<T>(m, l, cur, oth, dd, rr, di, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), s);
+      if (rc) return rc;
+      std::swap(cur, oth);
       rho = rho_new;
     }
     return check_hip(hipGetLastError(), "chebyshev");
   }
-  // the same polynomial continued from the current x (m operator applications)
+  // the same polynomial continued from the current x (m fused operator
+  // applications; an odd count ends in t and is copied back)
   template <typename T>
   int cheb_from(int l, T* xx, const T* bb, T* dd, T* tt, int deg, double lmin, double lmax) {
     const int64_t nn = n_of(l);
@@ -324,16 +313,24 @@ struct Solver {
     const T* di = dinv_of<T>(l);
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
     double rho = 1.0 / sigma;
-    int rc = Alev<T>(l, xx, tt);
-    if (rc) return rc;
-    hipLaunchKernelGGL((k_cheb_first_res<T>), dim3(g), dim3(256), 0, s, xx, dd, bb, tt, di, nn, (T)(1.0 / theta));
-    for (int k = 1; k < deg; ++k) {
-      if ((rc = Alev<T>(l, xx, tt))) return rc;
-      const double rho_new = 1.0 / (2.0 * sigma - rho);
-      hipLaunchKernelGGL((k_cheb_step<T>), dim3(g), dim3(256), 0, s, xx, dd, bb, tt, di, nn, (T)(rho_new * rho),
-                         (T)(2.0 * rho_new / delta));
-      rho = rho_new;
+    T* cur = xx;
+    T* oth = tt;
+    for (int k = 0; k < deg; ++k) {
+      T c1 = 0, c2 = (T)(1.0 / theta);
+      if (k > 0) {
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        c1 = (T)(rho_new * rho);
+        c2 = (T)(2.0 * rho_new / delta);
+        rho = rho_new;
+      }
+      if (l == 0) {
+        if (sizeof(T) == 8) ++applies64; else ++applies32;
+      }
+      int rc = launch_poisson_cheb<T>(m, l, cur, oth, dd, bb, di, c1, c2, s);
+      if (rc) return rc;
+      std::swap(cur, oth);
     }
+    if (cur != xx) hipLaunchKernelGGL((k_copy<T>), dim3(g), dim3(256), 0, s, xx, cur, nn);
     return check_hip(hipGetLastError(), "chebyshev");
   }
   // x = V-cycle(l) b: Chebyshev-Jacobi pre-smoothing, restricted residual,
@@ -356,8 +353,11 @@ struct Solver {
     }
     const double lmin = lam / kSmoothRange, lmax = 1.1 * lam;
     if ((rc = cheb_l<T>(l, x, b, d, t, deg, lmin, lmax))) return rc;
-    if ((rc = Alev<T>(l, x, t))) return rc;
-    hipLaunchKernelGGL((k_resid_t<T>), dim3(g), dim3(256), 0, s, r, b, t, nn);
+    if (l == 0) {
+      if (sizeof(T) == 8) ++applies64; else ++applies32;
+    }
+    if ((rc = launch_poisson_resid<T>(mm, l, x, b, r, s))) return rc;
+    (void)g;
     Lv& c = lv[l + 1];
     T* xc = reinterpret_cast<T*>(c.x);
     T* bc = reinterpret_cast<T*>(c.b);

@@ -48,6 +48,8 @@ class MeshConfig:
     ip_factor_p: float = 1.0
     wall_ip_mult: float = 10.0
     theta: float = 1.0
+    psi_kind: int = 0          # 0: Spalding's law, 1: van Driest's law
+    A_plus: float = 26.0
 
     def as_dict(self):
         return asdict(self)

@@ -217,3 +217,50 @@ def test_psi_field_chain_rule_and_wall_law():
             xc[1] = xm[1] + dlt
             assert abs(O.psi_point(cfg, tau, e, xc)[2] - fd) <= 1e-6 * abs(fd)
             assert abs(out[1]) <= 1e-14 * abs(out[2]) and abs(out[3]) <= 1e-14 * abs(out[2])
+
+
+# ---- van Driest's law (Sec. 3.2, eq. psi; Appendix A) -----------------------
+
+A_PLUS = 26.0
+
+
+def _vandriest_table():
+    rows = []
+    with open(os.path.join(HERE, "golden", "vandriest_table.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                i, y, p = line.split()
+                rows.append((int(i), float(y), float(p)))
+    return rows
+
+
+def test_vandriest_matches_paper_table():
+    # Table tab:psi: support values computed with 32-digit arithmetic, printed
+    # with 15 significant digits; the oracle integrates from 0 by composite Gauss
+    rows = _vandriest_table()
+    assert len(rows) == 9
+    for _, y, p in rows:
+        U, _ = O.vandriest(y, KAPPA, A_PLUS)
+        assert abs(U - p) <= 5e-15 * max(1.0, p), (y, U, p)
+
+
+def test_vandriest_derivative_and_limits():
+    k2a2 = (KAPPA / A_PLUS) ** 2
+    # dU/dy+ is the integrand (finite differences, central, O(h^2))
+    for y in [0.5, 7.0, 30.0, 100.0, 3000.0]:
+        h = 1e-3 * max(1.0, y)
+        Up, _ = O.vandriest(y + h, KAPPA, A_PLUS)
+        Um, _ = O.vandriest(y - h, KAPPA, A_PLUS)
+        _, dU = O.vandriest(y, KAPPA, A_PLUS)
+        assert abs((Up - Um) / (2 * h) - dU) <= 1e-6 * dU
+    # wall: f(s) = 1 - (kappa/A+)^2 s^4 (1 - s/A+) + O(s^6), so
+    # U = y+ - (kappa/A+)^2 (y+^5/5 - y+^6/(6 A+)) + O(y+^7)
+    for y in [1e-3, 1e-2, 5e-2]:
+        U, dU = O.vandriest(y, KAPPA, A_PLUS)
+        nxt = k2a2 * y ** 4 * (y / A_PLUS) ** 2
+        assert abs(U - (y - k2a2 * (y ** 5 / 5 - y ** 6 / (6 * A_PLUS)))) <= nxt * y + 1e-17
+        assert abs(dU - (1 - k2a2 * y ** 4 * (1 - y / A_PLUS))) <= 2 * nxt + 2e-16
+    # outer layer: f(s) -> 1/(kappa s), so U(2y) - U(y) -> ln(2)/kappa
+    U1, _ = O.vandriest(2000.0, KAPPA, A_PLUS)
+    U2, _ = O.vandriest(4000.0, KAPPA, A_PLUS)
+    assert abs((U2 - U1) - math.log(2.0) / KAPPA) < 2e-3
