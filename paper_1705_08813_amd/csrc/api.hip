@@ -51,6 +51,10 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
     return set_error(DG_ERR_ARG, "geometry or material parameter invalid");
   if (!(P.ip_factor_u > 0) || !(P.ip_factor_p > 0) || !(P.wall_ip_mult > 0))
     return set_error(DG_ERR_ARG, "penalty factors must be positive");
+  if (P.psi_kind != DG_PSI_SPALDING && P.psi_kind != DG_PSI_VANDRIEST)
+    return set_error(DG_ERR_ARG, "psi_kind must be DG_PSI_SPALDING or DG_PSI_VANDRIEST");
+  if (P.psi_kind == DG_PSI_VANDRIEST && !(P.A_plus > 0 && std::isfinite(P.A_plus)))
+    return set_error(DG_ERR_ARG, "A_plus must be positive and finite");
   if (P.wall_amp != 0.0 && P.fully_periodic) return set_error(DG_ERR_ARG, "a curved wall needs walls");
   if (!(std::fabs(P.wall_amp) < 0.9)) return set_error(DG_ERR_ARG, "wall amplitude must be below 0.9");
   m.P = P;
@@ -255,6 +259,7 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
     if (!rc) rc = check_hip(hipMemcpyAsync(m->wdist, wd.data(), sizeof(double) * wd.size(), hipMemcpyHostToDevice, s), "copy");
     if (!rc) rc = launch_geometry(m, s);
   }
+  if (P.psi_kind == DG_PSI_VANDRIEST) vandriest_table(P.kappa, P.A_plus, m->vd);
   if (!rc) rc = launch_psi(m, s);
   if (!rc && !m->curved) rc = launch_poisson_diag(m, s);
   if (!rc && m->mg_nlev > 0) {

@@ -5,6 +5,7 @@
 // w = 2 / ((1 - t^2) P_n'(t)^2).  Gauss-Lobatto nodes are the end points and
 // the roots of P_{n-1}'.  The nodal basis is evaluated in barycentric form.
 // Everything is mapped to the reference interval [0,1].
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -164,6 +165,33 @@ void fill_poisson_ops(int np, int nq, double* out) {
   for (int i = 0; i < np; ++i) out[o.nd1 + i] = d0[i];
   float* f = reinterpret_cast<float*>(out + o.f32);
   for (int i = 0; i < o.n; ++i) f[i] = (float)out[i];
+}
+
+// van Driest's law at the support points y+_i = 0, 5, 11, 24, 59, 144, 361,
+// 946, 2517 (the locations of the paper's Table tab:psi): composite 12-point
+// Gauss-Legendre on unit panels up to 64, then panels of 10 % of the abscissa
+// (the integrand is analytic, so every panel is exact to rounding).
+void vandriest_table(double kappa, double A_plus, VdTable& t) {
+  static const double ys[VdTable::N] = {0.0, 5.0, 11.0, 24.0, 59.0, 144.0, 361.0, 946.0, 2517.0};
+  double g[kMaxQ + 4], w[kMaxQ + 4];
+  gauss_rule(12, g, w);
+  auto f = [&](double s) {
+    const double m = 2.0 * kappa * s * (-std::expm1(-s / A_plus));
+    return 2.0 / (1.0 + std::sqrt(1.0 + m * m));
+  };
+  double acc = 0.0, a = 0.0;
+  for (int i = 0; i < VdTable::N; ++i) {
+    while (a < ys[i]) {
+      const double width = a < 64.0 ? 1.0 : 0.1 * a;
+      const double b = std::min(a + width, ys[i]);
+      double sum = 0.0;
+      for (int q = 0; q < 12; ++q) sum += w[q] * f(a + (b - a) * g[q]);
+      acc += (b - a) * sum;
+      a = b;
+    }
+    t.y[i] = ys[i];
+    t.psi[i] = acc;
+  }
 }
 
 }  // namespace dgwm

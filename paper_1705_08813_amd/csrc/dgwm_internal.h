@@ -114,6 +114,14 @@ struct MgLevel {
   double lam = 0.0;                   // cached Lanczos estimate of lmax(D^{-1} A)
 };
 
+// Support points of van Driest's law (the paper's Appendix A, Table
+// tab:psi locations) and U at them, computed at set-up.
+struct VdTable {
+  static constexpr int N = 9;
+  double y[N], psi[N];
+};
+void vandriest_table(double kappa, double A_plus, VdTable& t);
+
 // Levels of a box mesh: coarsen every direction that has an even cell count
 // (and keeps ny >= 2 between walls) while the level has more than
 // kCoarseTarget unknowns.
@@ -148,6 +156,7 @@ struct dg_mesh {
   double* meas = nullptr; // [cell][volume, six face areas]
   double* tauF = nullptr; // [cell][face] interior-penalty parameters
   double* wdist = nullptr; // [2][nx+1] distances to the wall of the vertex rows iy = 1 and iy = ny-1
+  dgwm::VdTable vd{};     // van Driest support table (psi_kind = DG_PSI_VANDRIEST)
   // pressure multigrid hierarchy (flat meshes): level 0 aliases hy/diag above
   int mg_nlev = 0;
   dgwm::MgLevel mg[dgwm::kMaxLevels];

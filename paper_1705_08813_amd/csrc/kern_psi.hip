@@ -4,6 +4,7 @@
 //   y+ = y_h sqrt(tau_w) / nu    (rho = 1)
 //   psi = U(y+) with U the root of Spalding's law
 //         y+ = U + exp(-kappa B) (exp(kappa U) - 1 - kappa U - (kappa U)^2/2 - (kappa U)^3/6)
+//   or van Driest's law (eq. psi), U = int_0^{y+} 2 ds / (1 + sqrt(1 + (2 kappa s (1 - exp(-s/A+)))^2))
 //   grad psi = U'(y+) sqrt(tau_w)/nu grad y_h
 //
 // y_h is the wall distance (flat walls: exact, since the linear interpolation
@@ -42,6 +43,29 @@ __device__ void spalding_root(double yp, double kappa, double B, double& U, doub
   dU = 1.0 / (1.0 + c * kappa * (expm1(k) - k - 0.5 * k * k));
 }
 
+// van Driest's law (Sec. 3.2, eq. psi) as in the paper's Appendix A: U at
+// the support point y+_i below y+ comes from the set-up table, the slice
+// [y+_i, y+] is integrated with the 9-point Gauss rule; dU/dy+ is the
+// integrand f(s) = 2 / (1 + sqrt(1 + (2 kappa s (1 - exp(-s/A+)))^2)).
+__device__ __forceinline__ double vandriest_f(double s, double kappa, double Ap) {
+  const double m = 2.0 * kappa * s * (-expm1(-s / Ap));
+  return 2.0 / (1.0 + sqrt(1.0 + m * m));
+}
+
+__device__ void vandriest_eval(double yp, double kappa, double Ap, const VdTable& tb, double& U, double& dU) {
+  constexpr auto& G = ct::tab<2, 9>;  // 9-point Gauss rule on [0,1] (the basis part is unused)
+  int i = 0;
+#pragma unroll
+  for (int j = 1; j < VdTable::N; ++j)
+    if (tb.y[j] <= yp) i = j;
+  const double a = tb.y[i], h = yp - a;
+  double sum = 0.0;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) sum += G.w[q] * vandriest_f(a + h * G.g[q], kappa, Ap);
+  U = tb.psi[i] + h * sum;
+  dU = vandriest_f(yp, kappa, Ap);
+}
+
 // pts: the NQ Gauss points of the wall-parallel rule followed by the NQY
 // points of the wall-normal rule (on [0,1]).
 // Curved lower wall: y_h is the bilinear (x, eta) interpolation of the vertex
@@ -52,7 +76,8 @@ template <int NQ, int NQY>
 __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, const double* __restrict__ eta,
                            const double* __restrict__ pts, const double* __restrict__ tau, double nu, double kappa,
                            double B, int64_t nenr, int psi_pts, double* __restrict__ psi,
-                           const double* __restrict__ geo, int geo_stride, const double* __restrict__ wdist) {
+                           const double* __restrict__ geo, int geo_stride, const double* __restrict__ wdist,
+                           int psi_kind, double A_plus, const VdTable vd) {
   constexpr int NPTS = NQ * NQY * NQ;
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gid >= nenr * psi_pts) return;
@@ -125,7 +150,10 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
   }
   const double st = sqrt(tw) / nu;
   double U, dU;
-  spalding_root(fmax(yh, 0.0) * st, kappa, B, U, dU);
+  if (psi_kind == DG_PSI_VANDRIEST)
+    vandriest_eval(fmax(yh, 0.0) * st, kappa, A_plus, vd, U, dU);
+  else
+    spalding_root(fmax(yh, 0.0) * st, kappa, B, U, dU);
   o[0] = U;
   o[1] = dU * st * gyh[0];
   o[2] = dU * st * gyh[1];
@@ -147,7 +175,8 @@ int launch_psi(const dg_mesh* m, hipStream_t s) {
   if (m->P.nq_u == a && m->P.nq_wn == b) {                                                                   \
     hipLaunchKernelGGL((psi_kernel<a, b>), dim3(nb), dim3(128), 0, s, m->P.nx, m->P.ny, m->P.nz, lower_slot, \
                        m->n_enr_layers, m->eta, pts, m->tau, m->P.nu, m->P.kappa, m->P.B, m->nenr,          \
-                       m->psi_pts, m->psi, m->geo, m->geo_stride, m->wdist);                                 \
+                       m->psi_pts, m->psi, m->geo, m->geo_stride, m->wdist, m->P.psi_kind, m->P.A_plus,      \
+                       m->vd);                                                                               \
     return check_hip(hipGetLastError(), "psi kernel launch");                                                \
   }
   DG_PSI_COMBOS(X)

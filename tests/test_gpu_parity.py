@@ -229,3 +229,33 @@ def test_curved_config_sampled():
             enr_rows += [off + 3 * k + c for c in range(3)]
     enr_rows = np.array(enr_rows)
     assert _rel(r[enr_rows], r_orc[enr_rows]) <= 1e-12
+
+
+# van Driest's enrichment (Sec. 3.2, eq. psi; Appendix A evaluation on the GPU,
+# composite Gauss from zero in the oracle).  The meshes span wall-cell y+ from
+# below the first support point to the 361..946 slice.
+VD_CASES = {
+    "vd_tiny": Workload("vd0", MeshConfig(nx=4, ny=4, nz=4, k_u=3, nq_u=4, k_p=2, nq_p=3, psi_kind=1), 41, 1.0, 1.0),
+    "vd_k4_stretched": Workload("vd1", MeshConfig(nx=3, ny=4, nz=2, gamma=1.8, k_u=4, nq_u=7, psi_kind=1), 42,
+                                0.5, 1.5),
+    "vd_k3_high_re": Workload("vd2", MeshConfig(nx=3, ny=3, nz=2, k_u=3, nq_u=5, psi_kind=1, nu=1.0 / 2000.0), 43,
+                              0.5, 2.0),
+    "vd_curved_k3": Workload("vd3", MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, k_p=2, nq_p=3,
+                                               psi_kind=1), 44, 0.2, 2.0),
+}
+
+
+@pytest.mark.parametrize("name", list(VD_CASES))
+def test_velocity_residual_vandriest_f64(name):
+    wl = VD_CASES[name]
+    _log(f"[gpu] velocity f64 van Driest case={name}")
+    inp = draw_inputs(wl)
+    r_orc = O.velocity_residual(wl.mesh, inp["u"], inp["tau"])
+    mesh = Mesh(wl.mesh, inp["tau"])
+    r = mesh.apply_velocity_residual(torch.tensor(inp["u"], device="cuda"))
+    torch.cuda.synchronize()
+    rp, re = _split(wl.mesh, r.cpu().numpy())
+    op, oe = _split(wl.mesh, r_orc)
+    _log(f"[gpu]   rel poly {_rel(rp, op):.2e} enr {_rel(re, oe):.2e}")
+    assert _rel(rp, op) <= 1e-12, _rel(rp, op)
+    assert _rel(re, oe) <= 1e-12, _rel(re, oe)
