@@ -218,6 +218,29 @@ def main():
                            "dofs_per_s": n_p / float(np.median(times))}
         extras["solve_speedup_mixed_vs_f64"] = extras["solve_f64"]["median_s"] / extras["solve_mixed"]["median_s"]
     if not args.no_extras:
+        # van Driest enrichment (eq. psi, Appendix A evaluation) on the same mesh: psi refresh and
+        # velocity residual (the residual kernel is the same; only the psi tables differ)
+        print("bench: van Driest enrichment", file=sys.stderr, flush=True)
+        vmesh = Mesh(m.with_(psi_kind=1), inp["tau"], device=dev)
+        for _ in range(3):
+            vmesh.update_wall_shear(tau)
+            vmesh.apply_velocity_residual(u, r)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        nrep = max(5, K // 2)
+        e0.record(stream)
+        for _ in range(nrep):
+            vmesh.update_wall_shear(tau)
+        e1.record(stream)
+        for _ in range(nrep):
+            vmesh.apply_velocity_residual(u, r)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        extras["vandriest"] = {"psi_refresh_ms": e0.elapsed_time(e1) / nrep,
+                               "velocity_ms": e1.elapsed_time(e2) / nrep,
+                               "psi_points": vmesh.n_enriched * (m.nq_u * m.nq_wn * m.nq_u + 2 * m.nq_u ** 2
+                                                                 + 4 * m.nq_u * m.nq_wn)}
+        del vmesh
+    if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)
         wc = PRESETS["curved"]

@@ -84,6 +84,8 @@ MG_CASES = {
     # two levels, coarsest (3x3x3, 1728 unknowns) too large for the dense inverse:
     # smoothed with the long Chebyshev polynomial instead
     "k3_cheb_coarse": MeshConfig(nx=6, ny=6, nz=6, gamma=1.0, k_p=3, nq_p=4, k_u=4, nq_u=7),
+    # highest compiled pressure degree, y-only partial coarsening at the end
+    "k5_pressure": MeshConfig(nx=4, ny=8, nz=2, gamma=1.5, k_p=5, nq_p=6, k_u=5, nq_u=8),
 }
 
 
