@@ -257,11 +257,15 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
 
   // Phase B1: lines along t1 (node i1 -> Gauss q1).  Fields: 0-2 value of
   // u_c, 3-5 normal derivative of u_c, 6 t1-derivative of u_D.
+  // (lines of field 6 come last, so only one wavefront runs both branches)
   for (int t = tid; t < 2 * 2 * 7 * NP; t += nt) {
-    const int i2 = t % NP;
-    int r = t / NP;
-    const int f = r % 7;
-    r /= 7;
+    constexpr int N0 = 2 * 2 * 6 * NP;
+    const bool last = t >= N0;
+    const int tt = last ? t - N0 : t;
+    const int i2 = tt % NP;
+    int r = tt / NP;
+    const int f = last ? 6 : r % 6;
+    if (!last) r /= 6;
     const int side = r % 2, s = r / 2;
     if (side == 1 && (s ? wall1 : wall0)) continue;
     const int c = f < 3 ? f : (f < 6 ? f - 3 : D);
@@ -294,11 +298,15 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
 
   // Phase C1: lines along t2 (node i2 -> Gauss q2), giving the 8 trace
   // fields of each side; field 7 = d_T2 u_D from the value of u_D.
+  // (lines of field 7 come last, so only one wavefront runs both branches)
   for (int t = tid; t < 2 * 2 * 8 * Q1; t += nt) {
-    const int q1 = t % Q1;
-    int r = t / Q1;
-    const int fo = r % 8;
-    r /= 8;
+    constexpr int N0 = 2 * 2 * 7 * Q1;
+    const bool last = t >= N0;
+    const int tt = last ? t - N0 : t;
+    const int q1 = tt % Q1;
+    int r = tt / Q1;
+    const int fo = last ? 7 : r % 7;
+    if (!last) r /= 7;
     const int side = r % 2, s = r / 2;
     if (side == 1 && (s ? wall1 : wall0)) continue;
     const int fin = fo < 7 ? fo : D;
@@ -414,10 +422,22 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   // Phase D1: lines along t2 transposed (q2 -> i2).  Tests 0-2: value test
   // S2^T fv_c (+ Sd2^T F[D][T2] / ht2 for c = D); 3: t1-derivative test
   // S2^T F[D][T1]; 4-6: normal-derivative test S2^T F[c][D].
+  // (the tests o = D, which add the Sd2 part, come last)
   for (int t = tid; t < 2 * 7 * Q1; t += nt) {
-    const int q1 = t % Q1;
-    int r = t / Q1;
-    const int o = r % 7, s = r / 7;
+    constexpr int N0 = 2 * 6 * Q1;
+    const bool last = t >= N0;
+    const int tt = last ? t - N0 : t;
+    const int q1 = tt % Q1;
+    int r = tt / Q1;
+    int o, s;
+    if (last) {
+      o = D;
+      s = r;
+    } else {
+      const int oi = r % 6;
+      o = oi < D ? oi : oi + 1;
+      s = r / 6;
+    }
     const int fin = o < 3 ? o : (o == 3 ? 6 : o - 1);
     const T* a = FL + (s * 8 + fin) * FP + q1;
     T x[Q2];
@@ -451,12 +471,25 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
 
   // Phase D2: lines along t1 transposed (q1 -> i1): value test of u_c on the
   // face layer, and the normal-derivative test (to be spread along D).
+  // (the value test of u_D, which adds the Sd1 part, comes last)
   for (int t = tid; t < 2 * 3 * 2 * NP; t += nt) {
-    const int i2 = t % NP;
-    int r = t / NP;
-    const int kind = r % 2;
-    r /= 2;
-    const int c = r % 3, s = r / 3;
+    constexpr int N0 = 2 * 5 * NP;
+    const bool last = t >= N0;
+    const int tt = last ? t - N0 : t;
+    const int i2 = tt % NP;
+    int r = tt / NP;
+    int kind, c, s;
+    if (last) {
+      kind = 0;
+      c = D;
+      s = r;
+    } else {
+      const int ci = r % 5;
+      const int pi = ci < 2 * D ? ci : ci + 1;  // (c, kind) pairs as c * 2 + kind, skipping (D, 0)
+      c = pi / 2;
+      kind = pi % 2;
+      s = r / 5;
+    }
     const T* a = B1 + ((s * 7 + (kind ? 4 + c : c)) * Q1) * NP + i2;
     T x[Q1];
 #pragma unroll
