@@ -59,6 +59,7 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
   if (!(std::fabs(P.wall_amp) < 0.9)) return set_error(DG_ERR_ARG, "wall amplitude must be below 0.9");
   m.P = P;
   m.ncell = (int64_t)P.nx * P.ny * P.nz;
+  if (m.ncell > INT32_MAX) return set_error(DG_ERR_ARG, "more than 2^31 - 1 cells");
   m.np_u = P.k_u + 1;
   m.np_p = P.k_p + 1;
   m.lower_slot = m.upper_slot = -1;

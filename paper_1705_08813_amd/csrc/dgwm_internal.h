@@ -188,9 +188,15 @@ int launch_poisson_resid(const dg_mesh* m, int level, const T* x, const T* b, T*
 template <typename T>
 int launch_poisson_cheb(const dg_mesh* m, int level, const T* z, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
                         hipStream_t s);
+// the same step from z = c0 dinv b (formed inside the kernel), d = v, zout = z + v
+template <typename T>
+int launch_poisson_cheb_first(const dg_mesh* m, int level, T c0, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
+                              hipStream_t s);
 // multigrid transfers between level l (fine) and l + 1 (coarse)
 int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s);
-int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, void* xf, hipStream_t s);
+// xo = xf + P xc (xo may be xf)
+int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, const void* xf, void* xo,
+                          hipStream_t s);
 // x = B b with the dense coarsest-level inverse B (n x n)
 int launch_dense_apply(int64_t n, dg_prec prec, const void* B, const void* b, void* x, hipStream_t s);
 // device workspace of dg_solve_poisson on mesh m

@@ -138,9 +138,10 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(const Tr tr, const T* 
   }
 }
 
-// xf += P xc on the fine cells of one coarse cell
+// xo = xf + P xc on the fine cells of one coarse cell (xo may be xf: each
+// entry is read and written by the same thread)
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* __restrict__ xc, T* __restrict__ xf) {
+__global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* __restrict__ xc, const T* xf, T* xo) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
   __shared__ T P[3 * 2 * NP * NP];
   __shared__ T S[NP3];      // [kc][jc][i]
@@ -183,31 +184,32 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* _
     for (int i = 0; i < NP; ++i) s += Px[(a * NP + l) * NP + i] * bb[i];
     const int fx = tr.cx ? 2 * X + a : X, fy = tr.cy ? 2 * Y + b : Y, fz = tr.cz ? 2 * Z + c : Z;
     const int64_t fe = fx + (int64_t)tr.nfx * (fy + (int64_t)tr.nfy * fz);
-    xf[fe * NP3 + node] += s;
+    xo[fe * NP3 + node] = xf[fe * NP3 + node] + s;
   }
 }
 
-// x = B b for a dense symmetric B (n x n, n <= kMaxCoarseDofs): b staged in
-// LDS, one thread per entry of x, four independent partial sums so that the
-// column loads of B stay in flight.
+// x = B b for a dense symmetric B (n x n, n <= kMaxCoarseDofs): one
+// wavefront per row, lanes stride along the row (coalesced), two partial sums
+// per lane and a butterfly reduction over the wavefront; four rows per
+// workgroup, so n / 4 workgroups share the matrix read.
 template <typename T>
 __global__ __launch_bounds__(256) void dense_apply_kernel(int n, const T* __restrict__ B, const T* __restrict__ b,
                                                           T* __restrict__ x) {
-  __shared__ T sb[kMaxCoarseDofs];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) sb[j] = b[j];
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  int j = 0;
-  for (; j + 4 <= n; j += 4) {
-    s0 += B[(int64_t)j * n + i] * sb[j];
-    s1 += B[(int64_t)(j + 1) * n + i] * sb[j + 1];
-    s2 += B[(int64_t)(j + 2) * n + i] * sb[j + 2];
-    s3 += B[(int64_t)(j + 3) * n + i] * sb[j + 3];
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;  // whole wavefronts leave together
+  const T* row = B + (int64_t)i * n;
+  T s0 = 0, s1 = 0;
+  int j = lane;
+  for (; j + 64 < n; j += 128) {
+    s0 += row[j] * b[j];
+    s1 += row[j + 64] * b[j + 64];
   }
-  for (; j < n; ++j) s0 += B[(int64_t)j * n + i] * sb[j];
-  x[i] = (s0 + s1) + (s2 + s3);
+  if (j < n) s0 += row[j] * b[j];
+  T v = s0 + s1;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) x[i] = v;
 }
 
 // columns of the n x n identity, one vector of n entries per column
@@ -260,17 +262,20 @@ int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, vo
   return set_error(DG_ERR_UNSUPPORTED, "multigrid transfer degree not compiled");
 }
 
-int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, void* xf, hipStream_t s) {
+int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, const void* xf, void* xo,
+                          hipStream_t s) {
   const Tr tr = make_tr(m, l);
   const unsigned nb = (unsigned)m->mg[l + 1].ncell;
 #define X(a)                                                                                                  \
   if (m->np_p == a) {                                                                                         \
     if (prec == DG_F64)                                                                                       \
       hipLaunchKernelGGL((mg_prolong_kernel<double, a>), dim3(nb), dim3(256), 0, s, tr,                       \
-                         static_cast<const double*>(xc), static_cast<double*>(xf));                           \
+                         static_cast<const double*>(xc), static_cast<const double*>(xf),                      \
+                         static_cast<double*>(xo));                                                           \
     else                                                                                                      \
       hipLaunchKernelGGL((mg_prolong_kernel<float, a>), dim3(nb), dim3(256), 0, s, tr,                        \
-                         static_cast<const float*>(xc), static_cast<float*>(xf));                             \
+                         static_cast<const float*>(xc), static_cast<const float*>(xf),                        \
+                         static_cast<float*>(xo));                                                            \
     return check_hip(hipGetLastError(), "prolongation launch");                                               \
   }
   DG_MG_NP(X)
@@ -280,7 +285,7 @@ int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc,
 
 int launch_dense_apply(int64_t n, dg_prec prec, const void* B, const void* b, void* x, hipStream_t s) {
   if (n > kMaxCoarseDofs) return set_error(DG_ERR_ARG, "dense coarse solve larger than its limit");
-  const unsigned nb = (unsigned)((n + 255) / 256);
+  const unsigned nb = (unsigned)((n + 3) / 4);  // four rows per workgroup
   if (prec == DG_F64)
     hipLaunchKernelGGL((dense_apply_kernel<double>), dim3(nb), dim3(256), 0, s, (int)n,
                        static_cast<const double*>(B), static_cast<const double*>(b), static_cast<double*>(x));

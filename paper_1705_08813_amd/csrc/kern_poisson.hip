@@ -13,19 +13,17 @@ namespace dgwm {
 
 namespace {
 
-// Neighbour of cell (ex, ey, ez) across face (D, S): -1 for a (Neumann)
-// wall.  ny1 receives the neighbour's layer index.
-__device__ __forceinline__ int64_t poi_nb(const MeshDev& M, int ex, int ey, int ez, int D, int S, int& ny1) {
-  int x = ex, yy = ey, z = ez;
-  int& j = D == 0 ? x : (D == 1 ? yy : z);
+// Neighbour of cell e = (ex, ey, ez) across face (D, S): -1 for a (Neumann)
+// wall.  Cell counts stay below 2^31 (checked at set-up).
+__device__ __forceinline__ int poi_nb(const MeshDev& M, int e, int ex, int ey, int ez, int D, int S) {
+  const int j = D == 0 ? ex : (D == 1 ? ey : ez);
   const int nmax = D == 0 ? M.nx : (D == 1 ? M.ny : M.nz);
-  j += S ? 1 : -1;
-  if (j < 0 || j >= nmax) {
+  const int step = D == 0 ? 1 : (D == 1 ? M.nx : M.nx * M.ny);
+  if (S ? j == nmax - 1 : j == 0) {
     if (D == 1 && !M.fully_periodic) return -1;
-    j = (j + nmax) % nmax;
+    return S ? e - (nmax - 1) * step : e + (nmax - 1) * step;
   }
-  ny1 = yy;
-  return x + (int64_t)M.nx * (yy + (int64_t)M.ny * z);
+  return S ? e + step : e - step;
 }
 
 // What the kernel does with y = A p at each output entry (solver fusion):
@@ -33,7 +31,10 @@ __device__ __forceinline__ int64_t poi_nb(const MeshDev& M, int ex, int ey, int 
 //   kResid: r = b - A p
 //   kCheb:  v = c1 d + c2 dinv (b - A p), d = v, zout = p + v (one step of
 //           the Chebyshev recurrence; zout must not alias p; c1 = 0 ignores d)
-enum PoiEpiKind { kPlain = 0, kResid = 1, kCheb = 2 };
+//   kChebFirst: the same step taken from the first Chebyshev iterate
+//           p = d = c0 dinv b, which the kernel forms from b as it loads it
+//           (the input pointer is b; d is only written)
+enum PoiEpiKind { kPlain = 0, kResid = 1, kCheb = 2, kChebFirst = 3 };
 template <typename T>
 struct PoiEpi {
   int kind;
@@ -41,7 +42,7 @@ struct PoiEpi {
   const T* dinv;
   T* d;
   T* zout;
-  T c1, c2;
+  T c1, c2, c0;
 };
 
 // Cells per workgroup: one thread per pencil (line of NP nodes), so a cell
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   const int a = t % NP, b = t / NP;
   const int64_t e = (int64_t)blk * CB + c;
   const bool live = tid < BL::NT && e < ncell;
+  const bool pre = E.kind == kChebFirst;
 
   constexpr PoiOps O = poi_ops(NP);
   const T* ops = sizeof(T) == 8 ? reinterpret_cast<const T*>(M.tab + M.ops_off)
@@ -116,18 +118,39 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   T* sZ = s_Z + c * NP3;
 
   T px[NP];
-  T vnb[3][2], dnb[3][2], hnb[3][2];
+  T eb[NP], ei_[NP], ed[NP];  // epilogue operands b, dinv, d, loaded with the input
+  T vnb[3][2], dnb[3][2], rnb[3][2];
   bool wall[3][2];
-  T h[3];
+  T h[3], rh[3];
   if (live) {
-    const int ex = (int)(e % M.nx), ey = (int)((e / M.nx) % M.ny), ez = (int)(e / ((int64_t)M.nx * M.ny));
+    const int ei = (int)e;
+    const int ex = ei % M.nx, eyz = ei / M.nx, ey = eyz % M.ny, ez = eyz / M.ny;
     h[0] = T(M.hx);
     h[1] = T(M.hy[ey]);
     h[2] = T(M.hz);
-    const T* pe = p + e * NP3;
-    const int bx = pencil_base<NP>(0, a, b);
 #pragma unroll
-    for (int l = 0; l < NP; ++l) px[l] = pe[bx + l];
+    for (int D = 0; D < 3; ++D) rh[D] = T(1) / h[D];
+    const int bx = pencil_base<NP>(0, a, b);
+    const int64_t o = e * NP3 + bx;
+    if (E.kind != kPlain) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) eb[l] = E.b[o + l];
+    }
+    if (E.kind >= kCheb) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) ei_[l] = E.dinv[o + l];
+    }
+    if (E.kind == kCheb && E.c1 != T(0)) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) ed[l] = E.d[o + l];
+    }
+    if (pre) {  // p is b
+#pragma unroll
+      for (int l = 0; l < NP; ++l) px[l] = E.c0 * ei_[l] * eb[l];
+    } else {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) px[l] = p[o + l];
+    }
 #pragma unroll
     for (int l = 0; l < NP; ++l) sP[bx + l] = px[l];
     // traces of the six neighbours on the shared faces: value and d/dx_D
@@ -136,26 +159,33 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
       const int bD = pencil_base<NP>(D, a, b);
 #pragma unroll
       for (int S = 0; S < 2; ++S) {
-        int ny1 = ey;
-        const int64_t nb = poi_nb(M, ex, ey, ez, D, S, ny1);
+        const int nb = poi_nb(M, ei, ex, ey, ez, D, S);
         wall[D][S] = nb < 0;
-        T v = 0, d = 0, hn = h[D];
+        T v = 0, d = 0, rn = rh[D];
         if (nb >= 0) {
-          const T* pn = p + nb * NP3 + bD;
+          const T* pn = p + (int64_t)nb * NP3 + bD;
           T q[NP];
 #pragma unroll
           for (int l = 0; l < NP; ++l) q[l] = pn[l * pencil_stride<NP>(D)];
+          if (pre) {
+            const T* dn = E.dinv + (int64_t)nb * NP3 + bD;
+#pragma unroll
+            for (int l = 0; l < NP; ++l) q[l] *= E.c0 * dn[l * pencil_stride<NP>(D)];
+          }
           // neighbour below (S = 0) meets us at its xi_D = 1, above (S = 1) at xi_D = 0
           const T* nd = S ? nd0 : nd1;
 #pragma unroll
           for (int l = 0; l < NP; ++l) d += nd[l] * q[l];
           v = S ? q[0] : q[NP - 1];
-          if (D == 1) hn = T(M.hy[ny1]);
-          d /= hn;
+          if (D == 1) {
+            const int yn = S ? (ey + 1 == M.ny ? 0 : ey + 1) : (ey == 0 ? M.ny - 1 : ey - 1);
+            rn = T(1) / T(M.hy[yn]);
+          }
+          d *= rn;
         }
         vnb[D][S] = v;
         dnb[D][S] = d;
-        hnb[D][S] = hn;
+        rnb[D][S] = rn;
       }
     }
   }
@@ -175,7 +205,7 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
 #pragma unroll
         for (int l = 0; l < NP; ++l) x[l] = sP[bD + l * pencil_stride<NP>(D)];
       }
-      const T hd = h[D];
+      const T rd = rh[D];
       const T area = D == 0 ? h[1] * h[2] : (D == 1 ? h[0] * h[2] : h[0] * h[1]);
       T d0 = 0, d1 = 0;
 #pragma unroll
@@ -183,20 +213,20 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
         d0 += nd0[l] * x[l];
         d1 += nd1[l] * x[l];
       }
-      d0 /= hd;
-      d1 /= hd;
+      d0 *= rd;
+      d1 *= rd;
       T J0 = 0, G0 = 0, J1 = 0, G1 = 0;
       if (!wall[D][0]) {  // face at xi_D = 0, outward sign -1
-        const T tau = pen * (T(1) / hd > T(1) / hnb[D][0] ? T(1) / hd : T(1) / hnb[D][0]);
+        const T tau = pen * (rd > rnb[D][0] ? rd : rnb[D][0]);
         J0 = x[0] - vnb[D][0];
         G0 = tau * J0 + T(0.5) * (d0 + dnb[D][0]);
       }
       if (!wall[D][1]) {  // face at xi_D = 1, outward sign +1
-        const T tau = pen * (T(1) / hd > T(1) / hnb[D][1] ? T(1) / hd : T(1) / hnb[D][1]);
+        const T tau = pen * (rd > rnb[D][1] ? rd : rnb[D][1]);
         J1 = x[NP - 1] - vnb[D][1];
         G1 = tau * J1 - T(0.5) * (d1 + dnb[D][1]);
       }
-      const T cv = area / hd;
+      const T cv = area * rd;
       T* dst = D == 0 ? sX : (D == 1 ? sY : sZ);
 #pragma unroll
       for (int l = 0; l < NP; ++l) {
@@ -275,10 +305,10 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
       if (E.kind == kPlain) {
         y[o + l] = s;
       } else if (E.kind == kResid) {
-        y[o + l] = E.b[o + l] - s;
+        y[o + l] = eb[l] - s;
       } else {
-        T v = E.c2 * E.dinv[o + l] * (E.b[o + l] - s);
-        if (E.c1 != T(0)) v += E.c1 * E.d[o + l];
+        T v = E.c2 * ei_[l] * (eb[l] - s);
+        if (E.c1 != T(0)) v += E.c1 * (pre ? px[l] : ed[l]);
         E.d[o + l] = v;
         E.zout[o + l] = px[l] + v;
       }
@@ -406,25 +436,32 @@ static int launch_poisson_t(const dg_mesh* m, int l, const T* p, T* y, hipStream
 int launch_poisson_level(const dg_mesh* m, int l, dg_prec prec, const void* p, void* y, hipStream_t s, int nvec,
                          int64_t vstride) {
   if (prec == DG_F64) {
-    const PoiEpi<double> E{kPlain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0};
+    const PoiEpi<double> E{kPlain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0};
     return launch_poisson_t<double>(m, l, static_cast<const double*>(p), static_cast<double*>(y), s, nvec, vstride,
                                     E);
   }
-  const PoiEpi<float> E{kPlain, nullptr, nullptr, nullptr, nullptr, 0.0f, 0.0f};
+  const PoiEpi<float> E{kPlain, nullptr, nullptr, nullptr, nullptr, 0.0f, 0.0f, 0.0f};
   return launch_poisson_t<float>(m, l, static_cast<const float*>(p), static_cast<float*>(y), s, nvec, vstride, E);
 }
 
 template <typename T>
 int launch_poisson_resid(const dg_mesh* m, int l, const T* x, const T* b, T* r, hipStream_t s) {
-  const PoiEpi<T> E{kResid, b, nullptr, nullptr, nullptr, T(0), T(0)};
+  const PoiEpi<T> E{kResid, b, nullptr, nullptr, nullptr, T(0), T(0), T(0)};
   return launch_poisson_t<T>(m, l, x, r, s, 1, 0, E);
 }
 
 template <typename T>
 int launch_poisson_cheb(const dg_mesh* m, int l, const T* z, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
                         hipStream_t s) {
-  const PoiEpi<T> E{kCheb, b, dinv, d, zout, c1, c2};
+  const PoiEpi<T> E{kCheb, b, dinv, d, zout, c1, c2, T(0)};
   return launch_poisson_t<T>(m, l, z, nullptr, s, 1, 0, E);
+}
+
+template <typename T>
+int launch_poisson_cheb_first(const dg_mesh* m, int l, T c0, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
+                              hipStream_t s) {
+  const PoiEpi<T> E{kChebFirst, b, dinv, d, zout, c1, c2, c0};
+  return launch_poisson_t<T>(m, l, b, nullptr, s, 1, 0, E);
 }
 
 template int launch_poisson_resid<double>(const dg_mesh*, int, const double*, const double*, double*, hipStream_t);
@@ -433,6 +470,10 @@ template int launch_poisson_cheb<double>(const dg_mesh*, int, const double*, dou
                                          const double*, double, double, hipStream_t);
 template int launch_poisson_cheb<float>(const dg_mesh*, int, const float*, float*, float*, const float*, const float*,
                                         float, float, hipStream_t);
+template int launch_poisson_cheb_first<double>(const dg_mesh*, int, double, double*, double*, const double*,
+                                               const double*, double, double, hipStream_t);
+template int launch_poisson_cheb_first<float>(const dg_mesh*, int, float, float*, float*, const float*, const float*,
+                                              float, float, hipStream_t);
 
 int launch_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, hipStream_t s) {
   return launch_poisson_level(m, 0, prec, p, y, s);

@@ -291,30 +291,33 @@ struct Solver {
     double rho = 1.0 / sigma;
     T* cur = ((deg - 1) % 2) ? tt : zz;
     T* oth = cur == zz ? tt : zz;
-    hipLaunchKernelGGL((k_cheb_first<T>), dim3(g), dim3(256), 0, s, cur, dd, rr, di, nn, (T)(1.0 / theta));
+    if (deg == 1)
+      hipLaunchKernelGGL((k_cheb_first<T>), dim3(g), dim3(256), 0, s, cur, dd, rr, di, nn, (T)(1.0 / theta));
     for (int k = 1; k < deg; ++k) {
       const double rho_new = 1.0 / (2.0 * sigma - rho);
       if (l == 0) {
         if (sizeof(T) == 8) ++applies64; else ++applies32;
       }
-      int rc = launch_poisson_cheb<T>(m, l, cur, oth, dd, rr, di, (T)(rho_new * rho), (T)(2.0 * rho_new / delta), s);
+      const T c1 = (T)(rho_new * rho), c2 = (T)(2.0 * rho_new / delta);
+      // the first application forms the first iterate D^{-1} r / theta itself
+      int rc = k == 1 ? launch_poisson_cheb_first<T>(m, l, (T)(1.0 / theta), oth, dd, rr, di, c1, c2, s)
+                      : launch_poisson_cheb<T>(m, l, cur, oth, dd, rr, di, c1, c2, s);
       if (rc) return rc;
       std::swap(cur, oth);
       rho = rho_new;
     }
     return check_hip(hipGetLastError(), "chebyshev");
   }
-  // the same polynomial continued from the current x (m fused operator
-  // applications; an odd count ends in t and is copied back)
+  // the same polynomial continued from the current iterate, which the
+  // caller has put in t for an odd step count and in x for an even one, so
+  // that the m fused operator applications end in x
   template <typename T>
   int cheb_from(int l, T* xx, const T* bb, T* dd, T* tt, int deg, double lmin, double lmax) {
-    const int64_t nn = n_of(l);
-    const unsigned g = grid_of(nn);
     const T* di = dinv_of<T>(l);
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
     double rho = 1.0 / sigma;
-    T* cur = xx;
-    T* oth = tt;
+    T* cur = (deg % 2) ? tt : xx;
+    T* oth = cur == xx ? tt : xx;
     for (int k = 0; k < deg; ++k) {
       T c1 = 0, c2 = (T)(1.0 / theta);
       if (k > 0) {
@@ -330,7 +333,6 @@ struct Solver {
       if (rc) return rc;
       std::swap(cur, oth);
     }
-    if (cur != xx) hipLaunchKernelGGL((k_copy<T>), dim3(g), dim3(256), 0, s, xx, cur, nn);
     return check_hip(hipGetLastError(), "chebyshev");
   }
   // x = V-cycle(l) b: Chebyshev-Jacobi pre-smoothing, restricted residual,
@@ -365,7 +367,8 @@ struct Solver {
     if ((rc = vcycle<T>(l + 1, xc, bc, reinterpret_cast<T*>(c.r), reinterpret_cast<T*>(c.d),
                         reinterpret_cast<T*>(c.t), deg)))
       return rc;
-    if ((rc = launch_mg_prolong_add(mm, l, prec, xc, x, s))) return rc;
+    // coarse correction into the buffer the post-smoothing starts from
+    if ((rc = launch_mg_prolong_add(mm, l, prec, xc, x, (deg % 2) ? t : x, s))) return rc;
     return cheb_from<T>(l, x, b, d, t, deg, lmin, lmax);
   }
   // Lanczos estimate of lmax(D^{-1} A_l) (20 Jacobi-PCG steps in FP64 on
