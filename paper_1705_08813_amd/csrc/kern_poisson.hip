@@ -64,6 +64,20 @@ __device__ __forceinline__ constexpr int pencil_stride(int D) {
   return D == 0 ? 1 : (D == 1 ? NP : NP * NP);
 }
 
+// LDS layout of one cell: node (i, j, k) at i + SJ j + SK k, cells SC apart.
+// The padding spreads the pencils that one wavefront reads or writes in the
+// same instruction (16 threads of a cell, one node each, along x, y or z)
+// over the LDS banks; the unpadded layout maps the NP = 4 pencils onto a
+// quarter of the banks.
+template <int NP>
+struct PoiLds {
+  static constexpr int SJ = NP, SK = NP * NP + (NP == 4 ? 1 : 0), SC = NP == 4 ? 76 : NP * NP * NP;
+  static __device__ __forceinline__ int base(int D, int a, int b) {
+    return D == 0 ? SJ * a + SK * b : (D == 1 ? a + SK * b : a + SJ * b);
+  }
+  static __device__ __forceinline__ constexpr int stride(int D) { return D == 0 ? 1 : (D == 1 ? SJ : SK); }
+};
+
 // Poisson operator on box cells.  On an affine box cell every term
 // separates: with the reference mass M and stiffness K of the 1-D basis
 // (built with the operator's Gauss rule, hence identical to quadrature),
@@ -78,7 +92,7 @@ __device__ __forceinline__ constexpr int pencil_stride(int D) {
 // every direction of its cell and reads the six neighbour pencils it needs
 // for the traces straight from global memory (no atomics: every output has
 // one writer).
-template <typename T, int NP>
+template <typename T, int NP, int KIND>
 __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y,
                                                       int64_t ncell, int nblocks, int64_t vstride,
                                                       const PoiEpi<T> E) {
@@ -87,10 +101,15 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   p += blockIdx.y * vstride;
   y += blockIdx.y * vstride;
   constexpr int NP2 = BL::NP2, NP3 = BL::NP3, CB = BL::CB;
-  __shared__ T s_P[CB * NP3];
-  __shared__ T s_X[CB * NP3];
-  __shared__ T s_Y[CB * NP3];
-  __shared__ T s_Z[CB * NP3];
+  using LD = PoiLds<NP>;
+  // In FP64 the input P and Q_x share one array (P is read into registers
+  // first, one more barrier) so that five workgroups fit in a CU's LDS; FP32
+  // keeps a separate input array.
+  constexpr bool kAlias = sizeof(T) == 8;
+  __shared__ T s_X[CB * LD::SC];
+  __shared__ T s_Y[CB * LD::SC];
+  __shared__ T s_Z[CB * LD::SC];
+  __shared__ T s_P[kAlias ? 1 : CB * LD::SC];
 
   // contiguous cell ranges per XCD (workgroups are dealt round-robin over 8)
   const int bid = blockIdx.x;
@@ -102,7 +121,9 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   const int a = t % NP, b = t / NP;
   const int64_t e = (int64_t)blk * CB + c;
   const bool live = tid < BL::NT && e < ncell;
-  const bool pre = E.kind == kChebFirst;
+  // the kind is a template argument so that the plain operator keeps no
+  // registers for the epilogue operands
+  constexpr bool pre = KIND == kChebFirst;
 
   constexpr PoiOps O = poi_ops(NP);
   const T* ops = sizeof(T) == 8 ? reinterpret_cast<const T*>(M.tab + M.ops_off)
@@ -112,10 +133,10 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   const T* nd0 = ops + O.nd0;
   const T* nd1 = ops + O.nd1;
 
-  T* sP = s_P + c * NP3;
-  T* sX = s_X + c * NP3;
-  T* sY = s_Y + c * NP3;
-  T* sZ = s_Z + c * NP3;
+  T* sX = s_X + c * LD::SC;
+  T* sY = s_Y + c * LD::SC;
+  T* sZ = s_Z + c * LD::SC;
+  T* sP = kAlias ? sX : s_P + c * LD::SC;
 
   T px[NP];
   T eb[NP], ei_[NP], ed[NP];  // epilogue operands b, dinv, d, loaded with the input
@@ -132,15 +153,15 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
     for (int D = 0; D < 3; ++D) rh[D] = T(1) / h[D];
     const int bx = pencil_base<NP>(0, a, b);
     const int64_t o = e * NP3 + bx;
-    if (E.kind != kPlain) {
+    if (KIND != kPlain) {
 #pragma unroll
       for (int l = 0; l < NP; ++l) eb[l] = E.b[o + l];
     }
-    if (E.kind >= kCheb) {
+    if (KIND >= kCheb) {
 #pragma unroll
       for (int l = 0; l < NP; ++l) ei_[l] = E.dinv[o + l];
     }
-    if (E.kind == kCheb && E.c1 != T(0)) {
+    if (KIND == kCheb && E.c1 != T(0)) {
 #pragma unroll
       for (int l = 0; l < NP; ++l) ed[l] = E.d[o + l];
     }
@@ -152,7 +173,7 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
       for (int l = 0; l < NP; ++l) px[l] = p[o + l];
     }
 #pragma unroll
-    for (int l = 0; l < NP; ++l) sP[bx + l] = px[l];
+    for (int l = 0; l < NP; ++l) sP[LD::base(0, a, b) + l] = px[l];
     // traces of the six neighbours on the shared faces: value and d/dx_D
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
@@ -191,20 +212,27 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   }
   __syncthreads();
 
+  // the thread's y and z pencils of P
+  T pyz[2][NP];
+  if (live) {
+#pragma unroll
+    for (int D = 1; D < 3; ++D) {
+      const int bD = LD::base(D, a, b);
+#pragma unroll
+      for (int l = 0; l < NP; ++l) pyz[D - 1][l] = sP[bD + l * LD::stride(D)];
+    }
+  }
+  if (kAlias) __syncthreads();
+
   // Q_D on the thread's pencil of every direction
   if (live) {
     const T pen = T(M.pen);
 #pragma unroll
     for (int D = 0; D < 3; ++D) {
-      const int bD = pencil_base<NP>(D, a, b);
+      const int bD = LD::base(D, a, b);
       T x[NP];
-      if (D == 0) {
 #pragma unroll
-        for (int l = 0; l < NP; ++l) x[l] = px[l];
-      } else {
-#pragma unroll
-        for (int l = 0; l < NP; ++l) x[l] = sP[bD + l * pencil_stride<NP>(D)];
-      }
+      for (int l = 0; l < NP; ++l) x[l] = D == 0 ? px[l] : pyz[D - 1][l];
       const T rd = rh[D];
       const T area = D == 0 ? h[1] * h[2] : (D == 1 ? h[0] * h[2] : h[0] * h[1]);
       T d0 = 0, d1 = 0;
@@ -236,7 +264,7 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
         T q = cv * (k + T(0.5) * nd0[l] * J0 - T(0.5) * nd1[l] * J1);
         if (l == 0) q += area * G0;
         if (l == NP - 1) q += area * G1;
-        dst[bD + l * pencil_stride<NP>(D)] = q;
+        dst[bD + l * LD::stride(D)] = q;
       }
     }
   }
@@ -244,8 +272,8 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
 
   // z sweeps: Y <- Mz Qy, X <- Mz Qx
   if (live) {
-    const int bz = pencil_base<NP>(2, a, b);
-    constexpr int sz = NP * NP;
+    const int bz = LD::base(2, a, b);
+    constexpr int sz = LD::SK;
     T u[NP], w[NP];
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
@@ -268,13 +296,14 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
 
   // y sweeps: Z <- My Qz + Y, X <- My X
   if (live) {
-    const int by = pencil_base<NP>(1, a, b);
+    const int by = LD::base(1, a, b);
+    constexpr int sy = LD::SJ;
     T u[NP], w[NP], v[NP];
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
-      u[l] = sZ[by + l * NP];
-      v[l] = sY[by + l * NP];
-      w[l] = sX[by + l * NP];
+      u[l] = sZ[by + l * sy];
+      v[l] = sY[by + l * sy];
+      w[l] = sX[by + l * sy];
     }
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
@@ -284,8 +313,8 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
         su += Mm[l * NP + m] * u[m];
         sw += Mm[l * NP + m] * w[m];
       }
-      sZ[by + l * NP] = su;
-      sX[by + l * NP] = sw;
+      sZ[by + l * sy] = su;
+      sX[by + l * sy] = sw;
     }
   }
   __syncthreads();
@@ -293,18 +322,19 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   // x sweep and write-out: y = Mx Z + X
   if (live) {
     const int bx = pencil_base<NP>(0, a, b);
+    const int lx = LD::base(0, a, b);
     T u[NP];
 #pragma unroll
-    for (int l = 0; l < NP; ++l) u[l] = sZ[bx + l];
+    for (int l = 0; l < NP; ++l) u[l] = sZ[lx + l];
     const int64_t o = e * NP3 + bx;
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
-      T s = sX[bx + l];
+      T s = sX[lx + l];
 #pragma unroll
       for (int m = 0; m < NP; ++m) s += Mm[l * NP + m] * u[m];
-      if (E.kind == kPlain) {
+      if (KIND == kPlain) {
         y[o + l] = s;
-      } else if (E.kind == kResid) {
+      } else if (KIND == kResid) {
         y[o + l] = eb[l] - s;
       } else {
         T v = E.c2 * ei_[l] * (eb[l] - s);
@@ -424,8 +454,23 @@ static int launch_poisson_t(const dg_mesh* m, int l, const T* p, T* y, hipStream
 #define X(a, b)                                                                                           \
   if (m->np_p == a && m->P.nq_p == b) {                                                                   \
     const int nb = (int)((ncell + PoiBlk<a>::CB - 1) / PoiBlk<a>::CB);                                    \
-    hipLaunchKernelGGL((poisson_kernel<T, a>), dim3(nb, nvec), dim3(256), 0, s, M, p, y, ncell, nb,       \
-                       vstride, E);                                                                       \
+    switch (E.kind) {                                                                                     \
+      case kPlain:                                                                                        \
+        hipLaunchKernelGGL((poisson_kernel<T, a, kPlain>), dim3(nb, nvec), dim3(256), 0, s, M, p, y, ncell, \
+                           nb, vstride, E);                                                               \
+        break;                                                                                            \
+      case kResid:                                                                                        \
+        hipLaunchKernelGGL((poisson_kernel<T, a, kResid>), dim3(nb, nvec), dim3(256), 0, s, M, p, y, ncell, \
+                           nb, vstride, E);                                                               \
+        break;                                                                                            \
+      case kCheb:                                                                                         \
+        hipLaunchKernelGGL((poisson_kernel<T, a, kCheb>), dim3(nb, nvec), dim3(256), 0, s, M, p, y, ncell,  \
+                           nb, vstride, E);                                                               \
+        break;                                                                                            \
+      default:                                                                                            \
+        hipLaunchKernelGGL((poisson_kernel<T, a, kChebFirst>), dim3(nb, nvec), dim3(256), 0, s, M, p, y,    \
+                           ncell, nb, vstride, E);                                                        \
+    }                                                                                                     \
     return check_hip(hipGetLastError(), "poisson kernel launch");                                         \
   }
   DG_POI_COMBOS(X)
