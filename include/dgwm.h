@@ -185,6 +185,8 @@ typedef struct {
   int32_t multigrid;    /* 1: the preconditioner is one geometric multigrid V-cycle whose        */
                         /*    smoother is the degree-cheb_degree Jacobi-Chebyshev polynomial;    */
                         /*    0: the polynomial alone (or the inner CG, see max_inner)           */
+  int32_t coarse_degree;/* multigrid: smoother degree on the levels below the finest           */
+                        /*    (0: cheb_degree; otherwise >= 1)                                   */
 } dg_solve_params;
 
 typedef struct {
@@ -211,10 +213,10 @@ int64_t dg_solve_workspace_bytes_for(const dg_mesh_params* params, const dg_solv
  * Preconditioner (the paper's solver is multigrid-preconditioned CG, Sec. 4.4):
  *   multigrid = 1: one V-cycle over the mesh's nested h-levels (cell pairs
  *     merged along every direction with an even count), smoothing by the
- *     degree-cheb_degree Chebyshev polynomial in D^{-1} A_l on
- *     [lmax_l/20, 1.1 lmax_l], transfers by the exact embedding of the coarse
- *     DG space and its transpose, the coarsest level by a dense
- *     pseudo-inverse; max_inner is ignored;
+ *     Chebyshev polynomial in D^{-1} A_l on [lmax_l/20, 1.1 lmax_l] of degree
+ *     cheb_degree on the finest level and coarse_degree below it, transfers
+ *     by the exact embedding of the coarse DG space and its transpose, the
+ *     coarsest level by a dense pseudo-inverse; max_inner is ignored;
  *   multigrid = 0: the Chebyshev polynomial on [lmax/30, 1.1 lmax] alone,
  *     optionally wrapped in max_inner FP32 CG iterations.
  * lmax of each level comes from 20 Lanczos steps and is cached in the mesh.

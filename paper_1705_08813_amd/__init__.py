@@ -102,9 +102,10 @@ class Mesh:
         _lib.check(_lib.lib().dg_update_wall_shear(self.handle, _dptr(tau_dev), _stream_ptr(stream)))
 
     def solve_params(self, rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5, inner_rtol=0.0,
-                     multigrid=True):
+                     multigrid=True, coarse_degree=3):
         return SolveParams(rtol=rtol, max_outer=max_outer, max_inner=max_inner, cheb_degree=cheb_degree,
-                           inner_rtol=inner_rtol, mixed=int(mixed), multigrid=int(multigrid))
+                           inner_rtol=inner_rtol, mixed=int(mixed), multigrid=int(multigrid),
+                           coarse_degree=coarse_degree)
 
     def solve_workspace(self, sp):
         import torch

@@ -7,8 +7,9 @@
 // accepting convergence.  Preconditioner:
 //   multigrid: one V-cycle over the mesh's nested levels (the paper's solver
 //              is multigrid-preconditioned, Sec. 4.4), Chebyshev-Jacobi
-//              smoothing, restriction/prolongation of kern_mg.hip, dense
-//              pseudo-inverse on the coarsest level;
+//              smoothing (degree m on the finest level, a separate, usually
+//              lower degree below it), restriction/prolongation of
+//              kern_mg.hip, dense pseudo-inverse on the coarsest level;
 //   otherwise: Chebyshev polynomial of degree m in D^{-1} A on
 //              [lmax/30, 1.1 lmax], optionally wrapped in FP32 CG iterations.
 // mixed = 1 runs the preconditioner in FP32 on the normalised residual.
@@ -339,7 +340,8 @@ struct Solver {
   // coarse correction, post-smoothing; the coarsest level is solved with the
   // dense pseudo-inverse (or smoothed with a long polynomial).
   template <typename T>
-  int vcycle(int l, T* x, const T* b, T* r, T* d, T* t, int deg) {
+  int vcycle(int l, T* x, const T* b, T* r, T* d, T* t, int deg0, int degc) {
+    const int deg = l == 0 ? deg0 : degc;  // smoothing degree on this level
     const dg_mesh* mm = m;
     const int L = nlev - 1;
     const int64_t nn = n_of(l);
@@ -351,7 +353,7 @@ struct Solver {
       if (mm->coarse_inv)
         return launch_dense_apply(nn, prec, sizeof(T) == 8 ? (const void*)mm->coarse_inv : (const void*)mm->coarse_inv32,
                                   b, x, s);
-      return cheb_l<T>(l, x, b, d, t, 4 * deg, lam / 200.0, 1.1 * lam);
+      return cheb_l<T>(l, x, b, d, t, 4 * deg0, lam / 200.0, 1.1 * lam);
     }
     const double lmin = lam / kSmoothRange, lmax = 1.1 * lam;
     if ((rc = cheb_l<T>(l, x, b, d, t, deg, lmin, lmax))) return rc;
@@ -365,7 +367,7 @@ struct Solver {
     T* bc = reinterpret_cast<T*>(c.b);
     if ((rc = launch_mg_restrict(mm, l, prec, r, bc, s))) return rc;
     if ((rc = vcycle<T>(l + 1, xc, bc, reinterpret_cast<T*>(c.r), reinterpret_cast<T*>(c.d),
-                        reinterpret_cast<T*>(c.t), deg)))
+                        reinterpret_cast<T*>(c.t), deg0, degc)))
       return rc;
     // coarse correction into the buffer the post-smoothing starts from
     if ((rc = launch_mg_prolong_add(mm, l, prec, xc, x, (deg % 2) ? t : x, s))) return rc;
@@ -488,7 +490,7 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   const auto t_start = std::chrono::steady_clock::now();
   if (!m || !sp || !b || !x || !ws) return set_error(DG_ERR_ARG, "mesh/params/b/x/workspace is NULL");
   if (ws_bytes < solve_bytes(m)) return set_error(DG_ERR_WORKSPACE, "solve workspace too small");
-  if (!(sp->rtol > 0) || sp->cheb_degree < 1 || sp->max_inner < 0 || sp->max_outer < 1)
+  if (!(sp->rtol > 0) || sp->cheb_degree < 1 || sp->coarse_degree < 0 || sp->max_inner < 0 || sp->max_outer < 1)
     return set_error(DG_ERR_ARG, "invalid solve parameters");
   if (b == x) return set_error(DG_ERR_ARG, "b and x must not alias");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Poisson operator is built for flat (box) meshes only");
@@ -549,6 +551,7 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   }
   const double lmax = 1.1 * mm->lam_max, lmin = mm->lam_max / 30.0;
   const int deg = sp->cheb_degree;
+  const int degc = sp->coarse_degree > 0 ? sp->coarse_degree : deg;
 
   // b' = b - mean(b), ||b'||
   hipLaunchKernelGGL((k_sum<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, b, S.n, S.part);
@@ -575,10 +578,10 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   };
   // preconditioner z = M^{-1} r
   auto precond = [&](double* zz) -> int {
-    if (use_mg && !sp->mixed) return S.vcycle<double>(0, zz, S.r, S.q, S.d64, S.t64, deg);
+    if (use_mg && !sp->mixed) return S.vcycle<double>(0, zz, S.r, S.q, S.d64, S.t64, deg, degc);
     if (use_mg) {
       hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR);
-      int e = S.vcycle<float>(0, S.x32, S.r32, S.rr32, S.d32, S.t32, deg);
+      int e = S.vcycle<float>(0, S.x32, S.r32, S.rr32, S.d32, S.t32, deg, degc);
       if (e) return e;
       hipLaunchKernelGGL(k_from_f32, dim3(S.grid), dim3(256), 0, S.s, zz, S.x32, S.n, sc + RR);
       return check_hip(hipGetLastError(), "preconditioner");

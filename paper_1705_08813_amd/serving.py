@@ -126,7 +126,8 @@ class Server:
         self.slots = int(slots)
         self.workers = int(workers)
         self.applies = int(applies)
-        kw = dict(rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5, multigrid=True)
+        kw = dict(rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5, multigrid=True,
+                  coarse_degree=3)
         kw.update(solve_kw or {})
         self.solve_kw = kw
         self.keep = keep_results
@@ -138,7 +139,7 @@ class Server:
         k = self.solve_kw
         return _lib.SolveParams(rtol=k["rtol"], max_outer=k["max_outer"], max_inner=k["max_inner"],
                                 cheb_degree=k["cheb_degree"], inner_rtol=0.0, mixed=int(k["mixed"]),
-                                multigrid=int(k["multigrid"]))
+                                multigrid=int(k["multigrid"]), coarse_degree=int(k["coarse_degree"]))
 
     # -- worker jobs (run on pool threads, each on its own stream) ---------
     def _stream(self):
