@@ -19,7 +19,11 @@
  *  - The library performs no device allocation: every device buffer,
  *    including the mesh tables and solver work vectors, lives in workspace
  *    that the caller allocates (e.g. a torch uint8 tensor) and keeps alive
- *    until dg_destroy_mesh / the end of the call that uses it.
+ *    until dg_destroy_mesh / the end of the call that uses it.  The mesh
+ *    handle holds one small pinned host buffer (freed by dg_destroy_mesh).
+ *  - Calls on different mesh handles may run concurrently from different
+ *    threads; two solves on one handle must not overlap (the handle caches
+ *    eigenvalue estimates and stages the solver's scalars).
  *
  * Mesh and numbering
  * ------------------
@@ -119,6 +123,7 @@ int64_t dg_num_dofs(const dg_mesh* mesh, int field);
 /* Number of enriched cells. */
 int64_t dg_num_enriched(const dg_mesh* mesh);
 
+/* Releases the handle and its pinned host buffer (not the caller's workspace). */
 void dg_destroy_mesh(dg_mesh* mesh);
 
 /* ----------------------------------------------------------- operators --- */
@@ -221,7 +226,9 @@ int64_t dg_solve_workspace_bytes_for(const dg_mesh_params* params, const dg_solv
  *     optionally wrapped in max_inner FP32 CG iterations.
  * lmax of each level comes from 20 Lanczos steps and is cached in the mesh.
  * With mixed = 1 the preconditioner runs in FP32 on the normalised residual.
- * Reads back one scalar per outer iteration and returns when converged.
+ * Reads back one scalar per outer iteration (the next preconditioner
+ * application is queued before the host waits for it) and returns when
+ * converged.
  *   b, x: device double vectors; workspace: dg_solve_workspace_bytes().
  *   Errors: DG_ERR_NOT_CONVERGED (stats filled) after max_outer iterations,
  *   DG_ERR_NONFINITE on NaN/Inf. */

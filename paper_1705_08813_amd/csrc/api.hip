@@ -274,6 +274,12 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
     delete m;
     return rc;
   }
+  // pinned slot for the solver's residual norms (the solver reads them back
+  // synchronously when this allocation is refused)
+  if (hipHostMalloc(reinterpret_cast<void**>(&m->host_sc), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    m->host_sc = nullptr;
+  }
   *out = m;
   return DG_OK;
 }
@@ -299,7 +305,10 @@ int64_t dg_num_enriched(const dg_mesh* m) {
   return m->nenr;
 }
 
-void dg_destroy_mesh(dg_mesh* m) { delete m; }
+void dg_destroy_mesh(dg_mesh* m) {
+  if (m && m->host_sc) (void)hipHostFree(m->host_sc);
+  delete m;
+}
 
 int dg_apply_velocity_residual(const dg_mesh* m, dg_prec prec, const void* u, void* r, void* stream) {
   if (!m || !u || !r) return set_error(DG_ERR_ARG, "mesh/u/r is NULL");

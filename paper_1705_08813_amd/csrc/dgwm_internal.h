@@ -139,6 +139,7 @@ struct dg_mesh {
   int lower_slot, upper_slot;  // enriched-layer slot of each wall or -1
   int psi_pts;            // points per enriched cell in the psi tables
   double hx, hz;
+  double* host_sc = nullptr;  // pinned host slots for scalars the solver reads back (nullptr: none)
   // device
   double* eta;            // ny+1 wall-normal vertex coordinates
   double* tab_u;          // velocity tables (np_u, nq_u, nq_wn)

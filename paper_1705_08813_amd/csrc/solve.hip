@@ -28,7 +28,7 @@ namespace dgwm {
 
 namespace {
 
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = 2048;  // eight blocks per CU keep enough loads in flight
 constexpr double kSmoothRange = 20.0;  // multigrid smoother interval [lmax / 20, 1.1 lmax]
 constexpr int kRedThreads = 256;
 
@@ -55,6 +55,26 @@ __global__ __launch_bounds__(kRedThreads) void k_dot(const TA* __restrict__ a, c
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
+// a.b1 and a.b2 in one pass (partials of the second at part + kRedBlocks)
+__global__ __launch_bounds__(kRedThreads) void k_dot2(const double* __restrict__ a, const double* __restrict__ b1,
+                                                      const double* __restrict__ b2, int64_t n,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  double v1 = 0, v2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double ai = a[i];
+    v1 += ai * b1[i];
+    v2 += ai * b2[i];
+  }
+  v1 = block_reduce(v1, sh);
+  __syncthreads();
+  v2 = block_reduce(v2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v1;
+    part[kRedBlocks + blockIdx.x] = v2;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_sum(const T* __restrict__ a, int64_t n, double* __restrict__ part) {
   __shared__ double sh[kRedThreads / 64];
@@ -65,13 +85,21 @@ __global__ __launch_bounds__(kRedThreads) void k_sum(const T* __restrict__ a, in
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// out = sum of the kRedBlocks partials (one block, fixed order).
-__global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict__ part, double* __restrict__ out) {
+// out[j] = sum of the kRedBlocks partials at part + j kRedBlocks, j < nout
+// (one block, fixed order).
+__global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict__ part, double* __restrict__ out,
+                                                       double* __restrict__ out2) {
   __shared__ double sh[kRedThreads / 64];
   double v = 0;
   for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[i];
   v = block_reduce(v, sh);
   if (threadIdx.x == 0) *out = v;
+  if (!out2) return;
+  __syncthreads();
+  v = 0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[kRedBlocks + i];
+  v = block_reduce(v, sh);
+  if (threadIdx.x == 0) *out2 = v;
 }
 
 template <typename T>
@@ -95,19 +123,28 @@ __global__ void k_resid(double* __restrict__ r, const double* __restrict__ b, co
     r[i] = b[i] - ax[i];
 }
 
-// x += alpha p, r -= alpha q with alpha = num/den (device scalars); partial sums of r^2.
+// x += alpha p, r -= alpha q with alpha = num/den (device scalars); partial
+// sums of r^2.  With r32 != nullptr the new residual is also written in FP32,
+// divided by sqrt(*rr_prev) (the previous residual norm, which keeps the FP32
+// copy near unit size); that divisor is stored in *scl for the way back.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_update_xr(T* __restrict__ x, T* __restrict__ r,
                                                           const T* __restrict__ p, const T* __restrict__ q, int64_t n,
                                                           const double* __restrict__ num,
-                                                          const double* __restrict__ den, double* __restrict__ part) {
+                                                          const double* __restrict__ den, double* __restrict__ part,
+                                                          float* __restrict__ r32 = nullptr,
+                                                          const double* __restrict__ rr_prev = nullptr,
+                                                          double* __restrict__ scl = nullptr) {
   __shared__ double sh[kRedThreads / 64];
   const T alpha = (T)(*num / *den);
+  const double nrm = r32 ? sqrt(*rr_prev) : 1.0, inv = 1.0 / nrm;
+  if (r32 && blockIdx.x == 0 && threadIdx.x == 0) *scl = nrm;
   double v = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
     const T ri = r[i] - alpha * q[i];
     r[i] = ri;
+    if (r32) r32[i] = (float)(ri * inv);
     v += (double)ri * (double)ri;
   }
   v = block_reduce(v, sh);
@@ -146,20 +183,46 @@ __global__ void k_cheb_step(T* __restrict__ z, T* __restrict__ d, const T* __res
   }
 }
 
-// out32 = r / sqrt(rr)
+// out32 = r / sqrt(rr); the divisor is stored in *scl
 __global__ void k_to_f32(float* __restrict__ out, const double* __restrict__ r, int64_t n,
-                         const double* __restrict__ rr) {
-  const double s = 1.0 / sqrt(*rr);
+                         const double* __restrict__ rr, double* __restrict__ scl) {
+  const double nrm = sqrt(*rr), s = 1.0 / nrm;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *scl = nrm;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (float)(r[i] * s);
 }
 
-// z = sqrt(rr) * x32
+// z = scl * x32
 __global__ void k_from_f32(double* __restrict__ z, const float* __restrict__ x, int64_t n,
-                           const double* __restrict__ rr) {
-  const double s = sqrt(*rr);
+                           const double* __restrict__ scl) {
+  const double s = *scl;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     z[i] = s * (double)x[i];
+}
+
+// z = scl * x32 together with the partial sums of r.z and (zold != nullptr)
+// r.zold (second set at part + kRedBlocks)
+__global__ __launch_bounds__(kRedThreads) void k_from_f32_dot2(double* __restrict__ z, const float* __restrict__ x,
+                                                               const double* __restrict__ scl,
+                                                               const double* __restrict__ r,
+                                                               const double* __restrict__ zold, int64_t n,
+                                                               double* __restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  const double s = *scl;
+  double v1 = 0, v2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double zi = s * (double)x[i], ri = r[i];
+    z[i] = zi;
+    v1 += ri * zi;
+    if (zold) v2 += ri * zold[i];
+  }
+  v1 = block_reduce(v1, sh);
+  __syncthreads();
+  v2 = block_reduce(v2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v1;
+    part[kRedBlocks + blockIdx.x] = v2;
+  }
 }
 
 template <typename T>
@@ -227,9 +290,14 @@ struct Solver {
   float *r32, *z32, *d32, *t32, *x32, *rr32, *pp32, *qq32, *dinv32;
   int applies64 = 0, applies32 = 0, inner_total = 0;
 
-  int red_final(double* out) {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, s, part, out);
+  int red_final(double* out, double* out2 = nullptr) {
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, s, part, out, out2);
     return check_hip(hipGetLastError(), "reduce");
+  }
+  // a.b1 -> out1, a.b2 -> out2 in one pass over a
+  int dot2(const double* a, const double* b1, const double* b2, double* out1, double* out2) {
+    hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b1, b2, n, part);
+    return red_final(out1, out2);
   }
   template <typename TA, typename TB>
   int dot(const TA* a, const TB* b, double* out, int64_t nn = -1) {
@@ -428,7 +496,7 @@ int Solver::lanczos(int l, double* out) {
     if ((rc = launch_poisson_level(m, l, DG_F64, p, q, s))) return rc;
     if ((rc = dot(p, q, PQ + k, nn))) return rc;
     hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, t64, r, p, q, nn, RZ + k,
-                       PQ + k, part);
+                       PQ + k, part, (float*)nullptr, (const double*)nullptr, (double*)nullptr);
   }
   double h[2 * K];
   if ((rc = check_hip(hipMemcpyAsync(h, RZ, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s), "lanczos copy")))
@@ -472,7 +540,7 @@ namespace dgwm {
 size_t solve_bytes_mesh(const dg_mesh& m) {
   const size_t n = (size_t)m.n_p;
   size_t b = 9 * up256(n * sizeof(double)) + 9 * up256(n * sizeof(float)) + up256(64 * sizeof(double)) +
-             up256(kRedBlocks * sizeof(double));
+             up256(2 * kRedBlocks * sizeof(double));
   for (int l = 1; l < m.mg_nlev; ++l) b += 7 * up256((size_t)m.mg[l].n * sizeof(double));
   return b;
 }
@@ -509,7 +577,7 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   S.sc = reinterpret_cast<double*>(w);
   w += up256(64 * sizeof(double));
   S.part = reinterpret_cast<double*>(w);
-  w += up256(kRedBlocks * sizeof(double));
+  w += up256(2 * kRedBlocks * sizeof(double));
   const bool use_mg = sp->multigrid && m->mg_nlev > 1;
   S.nlev = use_mg ? m->mg_nlev : 0;
   for (int l = 1; l < m->mg_nlev; ++l) {
@@ -525,7 +593,7 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
     v.dinv32 = reinterpret_cast<float*>(w); w += bytes;
   }
   double* sc = S.sc;
-  enum { RZ0 = 0, RZ1 = 1, PQ = 2, RR = 3, RZX = 4, SUM = 5, NB = 6, IRZ0 = 8, IRZ1 = 9, IPQ = 10, IRR = 11 };
+  enum { RZ0 = 0, RZ1 = 1, PQ = 2, RR = 3, RZX = 4, SUM = 5, NB = 6, SCL = 7, IRZ0 = 8, IRZ1 = 9, IPQ = 10, IRR = 11 };
   int rc;
 #define DG_TRY(expr) \
   if ((rc = (expr))) return rc
@@ -576,19 +644,15 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
     if (S.dot(S.r, S.r, sc + RR)) return NAN;
     return std::sqrt(S.host(sc + RR));
   };
-  // preconditioner z = M^{-1} r
-  auto precond = [&](double* zz) -> int {
+  // preconditioner z = M^{-1} r; r32_ready: the FP32 copy of r (and its
+  // scale in sc[SCL]) was already written by the residual update
+  auto precond = [&](double* zz, bool r32_ready) -> int {
     if (use_mg && !sp->mixed) return S.vcycle<double>(0, zz, S.r, S.q, S.d64, S.t64, deg, degc);
-    if (use_mg) {
-      hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR);
-      int e = S.vcycle<float>(0, S.x32, S.r32, S.rr32, S.d32, S.t32, deg, degc);
-      if (e) return e;
-      hipLaunchKernelGGL(k_from_f32, dim3(S.grid), dim3(256), 0, S.s, zz, S.x32, S.n, sc + RR);
-      return check_hip(hipGetLastError(), "preconditioner");
-    }
-    if (!sp->mixed) return S.cheb<double>(zz, S.r, S.d64, S.t64, S.dinv, deg, lmin, lmax);
+    if (!use_mg && !sp->mixed) return S.cheb<double>(zz, S.r, S.d64, S.t64, S.dinv, deg, lmin, lmax);
     // normalised FP32 copy of r (||r||^2 is in sc[RR])
-    hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR);
+    if (!r32_ready)
+      hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR, sc + SCL);
+    if (use_mg) return S.vcycle<float>(0, S.x32, S.r32, S.rr32, S.d32, S.t32, deg, degc);
     if (sp->max_inner == 0) {
       int e = S.cheb<float>(S.x32, S.r32, S.d32, S.t32, S.dinv32, deg, lmin, lmax);
       if (e) return e;
@@ -605,7 +669,8 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
         if ((e = S.A32(S.pp32, S.qq32))) return e;
         if ((e = S.dot(S.pp32, S.qq32, sc + IPQ))) return e;
         hipLaunchKernelGGL((k_update_xr<float>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, S.x32, S.rr32, S.pp32,
-                           S.qq32, S.n, sc + cur, sc + IPQ, S.part);
+                           S.qq32, S.n, sc + cur, sc + IPQ, S.part, (float*)nullptr, (const double*)nullptr,
+                           (double*)nullptr);
         ++S.inner_total;
         if (j + 1 == sp->max_inner) break;
         if ((e = S.cheb<float>(S.z32, S.rr32, S.d32, S.t32, S.dinv32, deg, lmin, lmax))) return e;
@@ -616,9 +681,32 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
         cur = nxt;
       }
     }
-    hipLaunchKernelGGL(k_from_f32, dim3(S.grid), dim3(256), 0, S.s, zz, S.x32, S.n, sc + RR);
     return check_hip(hipGetLastError(), "preconditioner");
   };
+  // z = M^{-1} r, then r.z -> *rz and (zold != nullptr) r.zold -> *rzx; the
+  // FP32 preconditioners return through the scaling pass, which forms the dot
+  // products on the way
+  auto precond_dots = [&](double* zz, bool r32_ready, const double* zold, double* rz, double* rzx) -> int {
+    int e = precond(zz, r32_ready);
+    if (e) return e;
+    if (!sp->mixed) return zold ? S.dot2(S.r, zz, zold, rz, rzx) : S.dot(S.r, zz, rz);
+    hipLaunchKernelGGL(k_from_f32_dot2, dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, zz, S.x32, sc + SCL, S.r, zold,
+                       S.n, S.part);
+    return S.red_final(rz, zold ? rzx : nullptr);
+  };
+
+  // the residual norm travels to the host through pinned memory, so the
+  // next preconditioner can be queued behind the copy and runs while the
+  // host waits for the norm (it touches neither x, r nor p)
+  double* hsc = m->host_sc;
+  hipEvent_t ev = nullptr;
+  if (hsc && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } ev_guard{ev};
 
   double rn = true_residual();
   if (!std::isfinite(rn)) return set_error(DG_ERR_NONFINITE, "non-finite residual");
@@ -626,18 +714,32 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   bool converged = rn <= sp->rtol * nb;
   const int max_it = sp->max_outer;
   const int replace_every = 50;
+  const bool fused32 = sp->mixed;  // the residual update writes the FP32 copy
   if (!converged) {
-    DG_TRY(precond(S.z));
+    DG_TRY(precond_dots(S.z, false, nullptr, sc + RZ0, nullptr));
     hipLaunchKernelGGL((k_copy<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n);
-    DG_TRY(S.dot(S.r, S.z, sc + RZ0));
     int cur = RZ0;
     for (it = 1; it <= max_it; ++it) {
       DG_TRY(S.A64(S.p, S.q));
       DG_TRY(S.dot(S.p, S.q, sc + PQ));
       hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, x, S.r, S.p, S.q, S.n,
-                         sc + cur, sc + PQ, S.part);
+                         sc + cur, sc + PQ, S.part, fused32 ? S.r32 : (float*)nullptr, (const double*)(sc + RR),
+                         sc + SCL);
       DG_TRY(S.red_final(sc + RR));
-      rn = std::sqrt(S.host(sc + RR));
+      std::swap(S.z, S.zold);
+      const int nxt = cur == RZ0 ? RZ1 : RZ0;
+      double rr;
+      if (ev) {
+        DG_TRY(check_hip(hipMemcpyAsync(hsc, sc + RR, sizeof(double), hipMemcpyDeviceToHost, S.s), "norm copy"));
+        DG_TRY(check_hip(hipEventRecord(ev, S.s), "event"));
+        DG_TRY(precond_dots(S.z, fused32, S.zold, sc + nxt, sc + RZX));
+        DG_TRY(check_hip(hipEventSynchronize(ev), "norm wait"));
+        rr = *hsc;
+      } else {
+        rr = S.host(sc + RR);
+        if (std::isfinite(rr)) DG_TRY(precond_dots(S.z, fused32, S.zold, sc + nxt, sc + RZX));
+      }
+      rn = std::sqrt(rr);
       if (!std::isfinite(rn)) return set_error(DG_ERR_NONFINITE, "non-finite residual");
       if (rn <= sp->rtol * nb || it % replace_every == 0) {
         rn = true_residual();
@@ -646,12 +748,9 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
           converged = true;
           break;
         }
+        // again from the recomputed residual
+        DG_TRY(precond_dots(S.z, false, S.zold, sc + nxt, sc + RZX));
       }
-      std::swap(S.z, S.zold);
-      DG_TRY(precond(S.z));
-      const int nxt = cur == RZ0 ? RZ1 : RZ0;
-      DG_TRY(S.dot(S.r, S.z, sc + nxt));
-      DG_TRY(S.dot(S.r, S.zold, sc + RZX));
       // flexible (Polak-Ribiere) beta = (r.z - r.z_old) / rz_old
       hipLaunchKernelGGL((k_update_p<double>), dim3(S.grid), dim3(256), 0, S.s, S.p, S.z, S.n, sc + nxt, sc + RZX,
                          sc + cur);
