@@ -188,6 +188,248 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* _
   }
 }
 
+// ---- levels coarsened along all three directions (the usual case) ----
+// Several coarse cells per workgroup, one thread per line of every sweep,
+// the x and z tables (uniform halves) as compile-time constants, the y table
+// of each coarse cell built in LDS, coalesced runs for the fine data.
+
+template <int NP>
+constexpr double lagrange_at(int i, double x) {
+  double v = 1.0;
+  for (int j = 0; j < NP; ++j)
+    if (j != i) v *= (x - ct::lobatto<NP>.x[j]) / (ct::lobatto<NP>.x[i] - ct::lobatto<NP>.x[j]);
+  return v;
+}
+// H[a][l][i] = N_i((a + x_l) / 2): child a of a uniformly halved direction
+template <int NP>
+struct HalfTab {
+  double v[2][NP][NP];
+  constexpr HalfTab() : v{} {
+    for (int a = 0; a < 2; ++a)
+      for (int l = 0; l < NP; ++l)
+        for (int i = 0; i < NP; ++i) v[a][l][i] = lagrange_at<NP>(i, 0.5 * (a + ct::lobatto<NP>.x[l]));
+  }
+};
+template <int NP>
+inline constexpr HalfTab<NP> half_tab{};
+
+constexpr int64_t kFullMinCells = 4096;  // coarse cells from which the batched transfer kernels pay off
+
+template <int NP>
+struct Full {
+  static constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
+  static constexpr int TPC = 4 * NP2;                       // threads per coarse cell (x-sweep lines)
+  static constexpr int CPC = 256 / TPC > 0 ? 256 / TPC : 1;  // coarse cells per workgroup
+};
+
+// Py[b][m][jc] of coarse cell cc into LDS (2 NP^2 entries per cell)
+template <typename T, int NP>
+__device__ __forceinline__ void build_py(T* Py, const Tr& tr, int64_t C0, int64_t ncc) {
+  constexpr int NP2 = NP * NP, CPC = Full<NP>::CPC;
+  constexpr auto& L = ct::lobatto<NP>;
+  for (int t = threadIdx.x; t < CPC * 2 * NP2; t += blockDim.x) {
+    const int cc = t / (2 * NP2), r = t % (2 * NP2);
+    const int jc = r % NP, m = (r / NP) % NP, b = r / NP2;
+    const int64_t C = C0 + cc;
+    double v = 0.0;
+    if (C < ncc) {
+      const int Y = ((int)C / tr.ncx) % tr.ncy;
+      const double h0 = tr.hyf[2 * Y], ry = h0 / (h0 + tr.hyf[2 * Y + 1]);
+      const double xc = b == 0 ? ry * L.x[m] : ry + (1.0 - ry) * L.x[m];
+      v = lobatto_basis<NP>(jc, xc);
+    }
+    Py[cc * 2 * NP2 + (b * NP + m) * NP + jc] = T(v);
+  }
+}
+
+// first entry of every child (a, b, c) of the workgroup's coarse cells
+// (-1 past the last coarse cell); cell counts stay below 2^31
+template <int NP>
+__device__ __forceinline__ void child_offsets(int64_t* off, const Tr& tr, int64_t C0, int64_t ncc) {
+  constexpr int NP3 = NP * NP * NP, CPC = Full<NP>::CPC;
+  for (int t = threadIdx.x; t < CPC * 8; t += blockDim.x) {
+    const int cc = t / 8, ch = t % 8, a = ch % 2, b = (ch / 2) % 2, c = ch / 4;
+    const int64_t C = C0 + cc;
+    if (C >= ncc) {
+      off[t] = -1;
+      continue;
+    }
+    const int Ci = (int)C, X = Ci % tr.ncx, YZ = Ci / tr.ncx, Y = YZ % tr.ncy, Z = YZ / tr.ncy;
+    const int fe = (2 * X + a) + tr.nfx * ((2 * Y + b) + tr.nfy * (2 * Z + c));
+    off[t] = (int64_t)fe * NP3;
+  }
+}
+
+// rc = P^T rf
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_restrict_full(const Tr tr, int64_t ncc, const T* __restrict__ rf,
+                                                        T* __restrict__ rc) {
+  using F = Full<NP>;
+  constexpr int NP2 = F::NP2, NP3 = F::NP3, CPC = F::CPC;
+  __shared__ T sF[CPC * 8 * NP3];  // [cc][c][b][a][k][j][l]
+  __shared__ T sG[CPC * 4 * NP3];  // [cc][c][b][k][j][i]
+  __shared__ T sH[CPC * 2 * NP3];  // [cc][c][k][jc][i]
+  __shared__ T sPy[CPC * 2 * NP2];
+  __shared__ int64_t sOff[CPC * 8];
+  const int64_t C0 = (int64_t)blockIdx.x * CPC;
+  build_py<T, NP>(sPy, tr, C0, ncc);
+  child_offsets<NP>(sOff, tr, C0, ncc);
+  __syncthreads();
+  // children: (a, node) runs are contiguous in memory
+  for (int t = threadIdx.x; t < CPC * 8 * NP3; t += blockDim.x) {
+    const int64_t o = sOff[t / NP3];
+    sF[t] = o >= 0 ? rf[o + t % NP3] : T(0);
+  }
+  __syncthreads();
+  constexpr auto& H = half_tab<NP>;
+  // x: G[c][b][k][j][i] = sum_a sum_l H[a][l][i] F[c][b][a][k][j][l]
+  for (int t = threadIdx.x; t < CPC * 4 * NP2; t += blockDim.x) {
+    const int cc = t / (4 * NP2), line = t % (4 * NP2);  // line = (c b k j), j fastest
+    const int kj = line % NP2, cb = line / NP2;
+    const T* f = sF + cc * 8 * NP3 + cb * 2 * NP3 + kj * NP;
+    T in[2][NP];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int l = 0; l < NP; ++l) in[a][l] = f[a * NP3 + l];
+    T* g = sG + cc * 4 * NP3 + cb * NP3 + kj * NP;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      T v = 0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int l = 0; l < NP; ++l) v += T(H.v[a][l][i]) * in[a][l];
+      g[i] = v;
+    }
+  }
+  __syncthreads();
+  // y: Hy[c][k][jc][i] = sum_b sum_m Py[b][m][jc] G[c][b][k][m][i]
+  for (int t = threadIdx.x; t < CPC * 2 * NP2; t += blockDim.x) {
+    const int cc = t / (2 * NP2), line = t % (2 * NP2);  // (c k i), i fastest
+    const int i = line % NP, k = (line / NP) % NP, c = line / NP2;
+    const T* py = sPy + cc * 2 * NP2;
+    T in[2][NP];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) in[b][m] = sG[cc * 4 * NP3 + (c * 2 + b) * NP3 + k * NP2 + m * NP + i];
+#pragma unroll
+    for (int jc = 0; jc < NP; ++jc) {
+      T v = 0;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) v += py[(b * NP + m) * NP + jc] * in[b][m];
+      sH[cc * 2 * NP3 + c * NP3 + k * NP2 + jc * NP + i] = v;
+    }
+  }
+  __syncthreads();
+  // z: rc[kc][jc][i] = sum_c sum_n H[c][n][kc] Hy[c][n][jc][i]
+  for (int t = threadIdx.x; t < CPC * NP2; t += blockDim.x) {
+    const int cc = t / NP2, ji = t % NP2;
+    const int64_t C = C0 + cc;
+    if (C >= ncc) continue;
+    T in[2][NP];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int n = 0; n < NP; ++n) in[c][n] = sH[cc * 2 * NP3 + c * NP3 + n * NP2 + ji];
+#pragma unroll
+    for (int kc = 0; kc < NP; ++kc) {
+      T v = 0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) v += T(H.v[c][n][kc]) * in[c][n];
+      rc[C * NP3 + kc * NP2 + ji] = v;
+    }
+  }
+}
+
+// xo = xf + P xc (xo may be xf: each entry is read and written by the same thread)
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_prolong_full(const Tr tr, int64_t ncc, const T* __restrict__ xc,
+                                                       const T* xf, T* xo) {
+  using F = Full<NP>;
+  constexpr int NP2 = F::NP2, NP3 = F::NP3, CPC = F::CPC;
+  __shared__ T sS[CPC * NP3];      // [cc][kc][jc][i]
+  __shared__ T sA[CPC * 2 * NP3];  // [cc][c][n][jc][i]
+  __shared__ T sB[CPC * 4 * NP3];  // [cc][c][b][n][m][i]
+  __shared__ T sF[CPC * 8 * NP3];  // [cc][c][b][a][n][m][l]
+  __shared__ T sPy[CPC * 2 * NP2];
+  __shared__ int64_t sOff[CPC * 8];
+  const int64_t C0 = (int64_t)blockIdx.x * CPC;
+  build_py<T, NP>(sPy, tr, C0, ncc);
+  child_offsets<NP>(sOff, tr, C0, ncc);
+  for (int t = threadIdx.x; t < CPC * NP3; t += blockDim.x) {
+    const int64_t C = C0 + t / NP3;
+    sS[t] = C < ncc ? xc[C0 * NP3 + t] : T(0);
+  }
+  __syncthreads();
+  constexpr auto& H = half_tab<NP>;
+  // z: A[c][n][jc][i] = sum_kc H[c][n][kc] S[kc][jc][i]
+  for (int t = threadIdx.x; t < CPC * NP2; t += blockDim.x) {
+    const int cc = t / NP2, ji = t % NP2;
+    T in[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) in[k] = sS[cc * NP3 + k * NP2 + ji];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int n = 0; n < NP; ++n) {
+        T v = 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) v += T(H.v[c][n][k]) * in[k];
+        sA[cc * 2 * NP3 + c * NP3 + n * NP2 + ji] = v;
+      }
+  }
+  __syncthreads();
+  // y: B[c][b][n][m][i] = sum_jc Py[b][m][jc] A[c][n][jc][i]
+  for (int t = threadIdx.x; t < CPC * 2 * NP2; t += blockDim.x) {
+    const int cc = t / (2 * NP2), line = t % (2 * NP2);  // (c n i), i fastest
+    const int i = line % NP, n = (line / NP) % NP, c = line / NP2;
+    const T* py = sPy + cc * 2 * NP2;
+    T in[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) in[j] = sA[cc * 2 * NP3 + c * NP3 + n * NP2 + j * NP + i];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        T v = 0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) v += py[(b * NP + m) * NP + j] * in[j];
+        sB[cc * 4 * NP3 + (c * 2 + b) * NP3 + n * NP2 + m * NP + i] = v;
+      }
+  }
+  __syncthreads();
+  // x: F[c][b][a][n][m][l] = sum_i H[a][l][i] B[c][b][n][m][i]
+  for (int t = threadIdx.x; t < CPC * 4 * NP2; t += blockDim.x) {
+    const int cc = t / (4 * NP2), line = t % (4 * NP2);  // (c b n m), m fastest
+    const int nm = line % NP2, cb = line / NP2;
+    T in[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) in[i] = sB[cc * 4 * NP3 + cb * NP3 + nm * NP + i];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        T v = 0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) v += T(H.v[a][l][i]) * in[i];
+        sF[cc * 8 * NP3 + (cb * 2 + a) * NP3 + nm * NP + l] = v;
+      }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < CPC * 8 * NP3; t += blockDim.x) {
+    const int64_t o0 = sOff[t / NP3];
+    if (o0 < 0) continue;
+    const int64_t o = o0 + t % NP3;
+    xo[o] = xf[o] + sF[t];
+  }
+}
+
 // x = B b for a dense symmetric B (n x n, n <= kMaxCoarseDofs): one
 // wavefront per row, lanes stride along the row (coalesced), two partial sums
 // per lane and a butterfly reduction over the wavefront; four rows per
@@ -246,7 +488,23 @@ Tr make_tr(const dg_mesh* m, int l) {
 
 int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s) {
   const Tr tr = make_tr(m, l);
-  const unsigned nb = (unsigned)m->mg[l + 1].ncell;
+  const int64_t ncc = m->mg[l + 1].ncell;
+  const unsigned nb = (unsigned)ncc;
+  // small levels are latency-bound: one workgroup per coarse cell finishes sooner there
+  const bool full = tr.cx && tr.cy && tr.cz && ncc >= kFullMinCells;
+#define X(a)                                                                                                  \
+  if (m->np_p == a && full) {                                                                                 \
+    const unsigned g = (unsigned)((ncc + Full<a>::CPC - 1) / Full<a>::CPC);                                   \
+    if (prec == DG_F64)                                                                                       \
+      hipLaunchKernelGGL((mg_restrict_full<double, a>), dim3(g), dim3(256), 0, s, tr, ncc,                    \
+                         static_cast<const double*>(rf), static_cast<double*>(rc));                           \
+    else                                                                                                      \
+      hipLaunchKernelGGL((mg_restrict_full<float, a>), dim3(g), dim3(256), 0, s, tr, ncc,                     \
+                         static_cast<const float*>(rf), static_cast<float*>(rc));                             \
+    return check_hip(hipGetLastError(), "restriction launch");                                                \
+  }
+  DG_MG_NP(X)
+#undef X
 #define X(a)                                                                                                  \
   if (m->np_p == a) {                                                                                         \
     if (prec == DG_F64)                                                                                       \
@@ -265,7 +523,25 @@ int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, vo
 int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, const void* xf, void* xo,
                           hipStream_t s) {
   const Tr tr = make_tr(m, l);
-  const unsigned nb = (unsigned)m->mg[l + 1].ncell;
+  const int64_t ncc = m->mg[l + 1].ncell;
+  const unsigned nb = (unsigned)ncc;
+  // small levels are latency-bound: one workgroup per coarse cell finishes sooner there
+  const bool full = tr.cx && tr.cy && tr.cz && ncc >= kFullMinCells;
+#define X(a)                                                                                                  \
+  if (m->np_p == a && full) {                                                                                 \
+    const unsigned g = (unsigned)((ncc + Full<a>::CPC - 1) / Full<a>::CPC);                                   \
+    if (prec == DG_F64)                                                                                       \
+      hipLaunchKernelGGL((mg_prolong_full<double, a>), dim3(g), dim3(256), 0, s, tr, ncc,                     \
+                         static_cast<const double*>(xc), static_cast<const double*>(xf),                      \
+                         static_cast<double*>(xo));                                                           \
+    else                                                                                                      \
+      hipLaunchKernelGGL((mg_prolong_full<float, a>), dim3(g), dim3(256), 0, s, tr, ncc,                      \
+                         static_cast<const float*>(xc), static_cast<const float*>(xf),                        \
+                         static_cast<float*>(xo));                                                            \
+    return check_hip(hipGetLastError(), "prolongation launch");                                               \
+  }
+  DG_MG_NP(X)
+#undef X
 #define X(a)                                                                                                  \
   if (m->np_p == a) {                                                                                         \
     if (prec == DG_F64)                                                                                       \

@@ -120,3 +120,28 @@ def test_multigrid_large_iteration_count():
     _log(f"[gpu] large multigrid its={st.outer_its} f32 applies={st.op_applies_f32} rel={st.rel_resid:.2e}")
     assert st.rel_resid <= 1e-10 and st.outer_its <= 30
     assert _oracle_relres(cfg, x.cpu().numpy(), b) <= 1.05e-10
+
+
+@pytest.mark.parametrize("k_p", [1, 2, 4])
+def test_multigrid_batched_transfers(k_p):
+    # 32^3 cells: the first coarsening has 4096 coarse cells, where the
+    # transfers switch to the kernels that batch several coarse cells per
+    # workgroup; 32x32x30 stays below that and uses one workgroup per coarse
+    # cell.  A wrong embedding or transpose would stall the V-cycle, so the
+    # batched path must converge as fast as the per-cell one.
+    its = {}
+    for nz in (32, 30):
+        cfg = MeshConfig(nx=32, ny=32, nz=nz, gamma=1.5, k_p=k_p, nq_p=k_p + 1, k_u=2, nq_u=4)
+        b = np.random.default_rng(40 + k_p).uniform(-1, 1, cfg.n_p)
+        mesh = Mesh(cfg)
+        bt = torch.tensor(b, device="cuda")
+        x, st = mesh.solve_poisson(bt, sp=mesh.solve_params(mixed=True, multigrid=True))
+        _log(f"[gpu] transfers k_p={k_p} nz={nz} its={st.outer_its} rel={st.rel_resid:.2e}")
+        assert st.rel_resid <= 1e-10
+        its[nz] = st.outer_its
+        if k_p == 1 and nz == 32:
+            xa = x.cpu().numpy()
+            assert _oracle_relres(cfg, xa, b) <= 1.05e-10
+            x2, _ = mesh.solve_poisson(bt, sp=mesh.solve_params(mixed=False, multigrid=False))
+            assert np.linalg.norm(xa - x2.cpu().numpy()) <= 1e-7 * np.linalg.norm(xa)
+    assert its[32] <= its[30] + 2, its
