@@ -183,16 +183,18 @@ int launch_poisson_level(const dg_mesh* m, int level, dg_prec prec, const void* 
                          int nvec = 1, int64_t vstride = 0);
 int launch_poisson_diag_level(const dg_mesh* m, int level, hipStream_t s);
 // fused solver steps on level l: r = b - A x, and one Chebyshev step
-// v = c1 d + c2 dinv (b - A z), d = v, zout = z + v (zout != z)
+// zout = z + c1 (z - zprev) + c2 dinv (b - A z), where zout holds the previous
+// iterate zprev on entry (zout != z)
 template <typename T>
 int launch_poisson_resid(const dg_mesh* m, int level, const T* x, const T* b, T* r, hipStream_t s);
 template <typename T>
-int launch_poisson_cheb(const dg_mesh* m, int level, const T* z, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
+int launch_poisson_cheb(const dg_mesh* m, int level, const T* z, T* zout, const T* b, const T* dinv, T c1, T c2,
                         hipStream_t s);
-// the same step from z = c0 dinv b (formed inside the kernel), d = v, zout = z + v
+// the same step from z = c0 dinv b (formed inside the kernel, zprev = 0),
+// which is also written to z1
 template <typename T>
-int launch_poisson_cheb_first(const dg_mesh* m, int level, T c0, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
-                              hipStream_t s);
+int launch_poisson_cheb_first(const dg_mesh* m, int level, T c0, T* zout, T* z1, const T* b, const T* dinv, T c1,
+                              T c2, hipStream_t s);
 // multigrid transfers between level l (fine) and l + 1 (coarse)
 int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s);
 // xo = xf + P xc (xo may be xf)

@@ -29,18 +29,20 @@ __device__ __forceinline__ int poi_nb(const MeshDev& M, int e, int ex, int ey, i
 // What the kernel does with y = A p at each output entry (solver fusion):
 //   kPlain: y = A p
 //   kResid: r = b - A p
-//   kCheb:  v = c1 d + c2 dinv (b - A p), d = v, zout = p + v (one step of
-//           the Chebyshev recurrence; zout must not alias p; c1 = 0 ignores d)
-//   kChebFirst: the same step taken from the first Chebyshev iterate
-//           p = d = c0 dinv b, which the kernel forms from b as it loads it
-//           (the input pointer is b; d is only written)
+//   kCheb:  v = c1 (p - zprev) + c2 dinv (b - A p), zout = p + v: one step
+//           of the Chebyshev recurrence, whose previous iterate zprev is read
+//           from zout before it is overwritten (c1 = 0: not read); zout must
+//           not alias p
+//   kChebFirst: the same step from the first iterate p = c0 dinv b (zprev =
+//           0), which the kernel forms from b as it loads it (the input
+//           pointer is b); p itself is written to z1 for the next step
 enum PoiEpiKind { kPlain = 0, kResid = 1, kCheb = 2, kChebFirst = 3 };
 template <typename T>
 struct PoiEpi {
   int kind;
   const T* b;
   const T* dinv;
-  T* d;
+  T* z1;
   T* zout;
   T c1, c2, c0;
 };
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
     }
     if (KIND == kCheb && E.c1 != T(0)) {
 #pragma unroll
-      for (int l = 0; l < NP; ++l) ed[l] = E.d[o + l];
+      for (int l = 0; l < NP; ++l) ed[l] = E.zout[o + l];
     }
     if (pre) {  // p is b
 #pragma unroll
@@ -338,8 +340,8 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
         y[o + l] = eb[l] - s;
       } else {
         T v = E.c2 * ei_[l] * (eb[l] - s);
-        if (E.c1 != T(0)) v += E.c1 * (pre ? px[l] : ed[l]);
-        E.d[o + l] = v;
+        if (E.c1 != T(0)) v += E.c1 * (pre ? px[l] : px[l] - ed[l]);
+        if (pre) E.z1[o + l] = px[l];
         E.zout[o + l] = px[l] + v;
       }
     }
@@ -496,25 +498,25 @@ int launch_poisson_resid(const dg_mesh* m, int l, const T* x, const T* b, T* r, 
 }
 
 template <typename T>
-int launch_poisson_cheb(const dg_mesh* m, int l, const T* z, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
+int launch_poisson_cheb(const dg_mesh* m, int l, const T* z, T* zout, const T* b, const T* dinv, T c1, T c2,
                         hipStream_t s) {
-  const PoiEpi<T> E{kCheb, b, dinv, d, zout, c1, c2, T(0)};
+  const PoiEpi<T> E{kCheb, b, dinv, nullptr, zout, c1, c2, T(0)};
   return launch_poisson_t<T>(m, l, z, nullptr, s, 1, 0, E);
 }
 
 template <typename T>
-int launch_poisson_cheb_first(const dg_mesh* m, int l, T c0, T* zout, T* d, const T* b, const T* dinv, T c1, T c2,
+int launch_poisson_cheb_first(const dg_mesh* m, int l, T c0, T* zout, T* z1, const T* b, const T* dinv, T c1, T c2,
                               hipStream_t s) {
-  const PoiEpi<T> E{kChebFirst, b, dinv, d, zout, c1, c2, c0};
+  const PoiEpi<T> E{kChebFirst, b, dinv, z1, zout, c1, c2, c0};
   return launch_poisson_t<T>(m, l, b, nullptr, s, 1, 0, E);
 }
 
 template int launch_poisson_resid<double>(const dg_mesh*, int, const double*, const double*, double*, hipStream_t);
 template int launch_poisson_resid<float>(const dg_mesh*, int, const float*, const float*, float*, hipStream_t);
-template int launch_poisson_cheb<double>(const dg_mesh*, int, const double*, double*, double*, const double*,
-                                         const double*, double, double, hipStream_t);
-template int launch_poisson_cheb<float>(const dg_mesh*, int, const float*, float*, float*, const float*, const float*,
-                                        float, float, hipStream_t);
+template int launch_poisson_cheb<double>(const dg_mesh*, int, const double*, double*, const double*, const double*,
+                                         double, double, hipStream_t);
+template int launch_poisson_cheb<float>(const dg_mesh*, int, const float*, float*, const float*, const float*, float,
+                                        float, hipStream_t);
 template int launch_poisson_cheb_first<double>(const dg_mesh*, int, double, double*, double*, const double*,
                                                const double*, double, double, hipStream_t);
 template int launch_poisson_cheb_first<float>(const dg_mesh*, int, float, float*, float*, const float*, const float*,

@@ -326,7 +326,6 @@ struct Solver {
     char* x;
     char* b;
     char* r;
-    char* d;
     char* t;
     double* dinv64;
     float* dinv32;
@@ -349,10 +348,11 @@ struct Solver {
   }
   int64_t n_of(int l) const { return l == 0 ? n : lv[l].n; }
   // z = Cheb_m(D^{-1} A_l) D^{-1} r from a zero start (m - 1 operator
-  // applications, each fused with its recurrence step; the iterate ping-pongs
-  // between z and t and is arranged to end in z)
+  // applications, each fused with its recurrence step).  The iterates
+  // ping-pong between z and t, each step overwriting the iterate before the
+  // previous one (which the kernel reads first), arranged to end in z.
   template <typename T>
-  int cheb_l(int l, T* zz, const T* rr, T* dd, T* tt, int deg, double lmin, double lmax) {
+  int cheb_l(int l, T* zz, const T* rr, T* tt, int deg, double lmin, double lmax) {
     const int64_t nn = n_of(l);
     const unsigned g = grid_of(nn);
     const T* di = dinv_of<T>(l);
@@ -360,8 +360,8 @@ struct Solver {
     double rho = 1.0 / sigma;
     T* cur = ((deg - 1) % 2) ? tt : zz;
     T* oth = cur == zz ? tt : zz;
-    if (deg == 1)
-      hipLaunchKernelGGL((k_cheb_first<T>), dim3(g), dim3(256), 0, s, cur, dd, rr, di, nn, (T)(1.0 / theta));
+    if (deg == 1)  // (the second output is scratch)
+      hipLaunchKernelGGL((k_cheb_first<T>), dim3(g), dim3(256), 0, s, cur, oth, rr, di, nn, (T)(1.0 / theta));
     for (int k = 1; k < deg; ++k) {
       const double rho_new = 1.0 / (2.0 * sigma - rho);
       if (l == 0) {
@@ -369,8 +369,9 @@ struct Solver {
       }
       const T c1 = (T)(rho_new * rho), c2 = (T)(2.0 * rho_new / delta);
       // the first application forms the first iterate D^{-1} r / theta itself
-      int rc = k == 1 ? launch_poisson_cheb_first<T>(m, l, (T)(1.0 / theta), oth, dd, rr, di, c1, c2, s)
-                      : launch_poisson_cheb<T>(m, l, cur, oth, dd, rr, di, c1, c2, s);
+      // and stores it in cur, where the second one finds it
+      int rc = k == 1 ? launch_poisson_cheb_first<T>(m, l, (T)(1.0 / theta), oth, cur, rr, di, c1, c2, s)
+                      : launch_poisson_cheb<T>(m, l, cur, oth, rr, di, c1, c2, s);
       if (rc) return rc;
       std::swap(cur, oth);
       rho = rho_new;
@@ -381,7 +382,7 @@ struct Solver {
   // caller has put in t for an odd step count and in x for an even one, so
   // that the m fused operator applications end in x
   template <typename T>
-  int cheb_from(int l, T* xx, const T* bb, T* dd, T* tt, int deg, double lmin, double lmax) {
+  int cheb_from(int l, T* xx, const T* bb, T* tt, int deg, double lmin, double lmax) {
     const T* di = dinv_of<T>(l);
     const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
     double rho = 1.0 / sigma;
@@ -398,7 +399,7 @@ struct Solver {
       if (l == 0) {
         if (sizeof(T) == 8) ++applies64; else ++applies32;
       }
-      int rc = launch_poisson_cheb<T>(m, l, cur, oth, dd, bb, di, c1, c2, s);
+      int rc = launch_poisson_cheb<T>(m, l, cur, oth, bb, di, c1, c2, s);
       if (rc) return rc;
       std::swap(cur, oth);
     }
@@ -408,12 +409,11 @@ struct Solver {
   // coarse correction, post-smoothing; the coarsest level is solved with the
   // dense pseudo-inverse (or smoothed with a long polynomial).
   template <typename T>
-  int vcycle(int l, T* x, const T* b, T* r, T* d, T* t, int deg0, int degc) {
+  int vcycle(int l, T* x, const T* b, T* r, T* t, int deg0, int degc) {
     const int deg = l == 0 ? deg0 : degc;  // smoothing degree on this level
     const dg_mesh* mm = m;
     const int L = nlev - 1;
     const int64_t nn = n_of(l);
-    const unsigned g = grid_of(nn);
     const double lam = mm->mg[l].lam;
     const dg_prec prec = sizeof(T) == 8 ? DG_F64 : DG_F32;
     int rc;
@@ -421,25 +421,23 @@ struct Solver {
       if (mm->coarse_inv)
         return launch_dense_apply(nn, prec, sizeof(T) == 8 ? (const void*)mm->coarse_inv : (const void*)mm->coarse_inv32,
                                   b, x, s);
-      return cheb_l<T>(l, x, b, d, t, 4 * deg0, lam / 200.0, 1.1 * lam);
+      return cheb_l<T>(l, x, b, t, 4 * deg0, lam / 200.0, 1.1 * lam);
     }
     const double lmin = lam / kSmoothRange, lmax = 1.1 * lam;
-    if ((rc = cheb_l<T>(l, x, b, d, t, deg, lmin, lmax))) return rc;
+    if ((rc = cheb_l<T>(l, x, b, t, deg, lmin, lmax))) return rc;
     if (l == 0) {
       if (sizeof(T) == 8) ++applies64; else ++applies32;
     }
     if ((rc = launch_poisson_resid<T>(mm, l, x, b, r, s))) return rc;
-    (void)g;
     Lv& c = lv[l + 1];
     T* xc = reinterpret_cast<T*>(c.x);
     T* bc = reinterpret_cast<T*>(c.b);
     if ((rc = launch_mg_restrict(mm, l, prec, r, bc, s))) return rc;
-    if ((rc = vcycle<T>(l + 1, xc, bc, reinterpret_cast<T*>(c.r), reinterpret_cast<T*>(c.d),
-                        reinterpret_cast<T*>(c.t), deg0, degc)))
+    if ((rc = vcycle<T>(l + 1, xc, bc, reinterpret_cast<T*>(c.r), reinterpret_cast<T*>(c.t), deg0, degc)))
       return rc;
     // coarse correction into the buffer the post-smoothing starts from
     if ((rc = launch_mg_prolong_add(mm, l, prec, xc, x, (deg % 2) ? t : x, s))) return rc;
-    return cheb_from<T>(l, x, b, d, t, deg, lmin, lmax);
+    return cheb_from<T>(l, x, b, t, deg, lmin, lmax);
   }
   // Lanczos estimate of lmax(D^{-1} A_l) (20 Jacobi-PCG steps in FP64 on
   // level l, using the level-0 work vectors, which are at least as long)
@@ -535,13 +533,13 @@ size_t solve_bytes(const dg_mesh* m) { return dgwm::solve_bytes_mesh(*m); }
 
 namespace dgwm {
 // 9 FP64 and 9 FP32 vectors of the fine level, scalars and partial sums,
-// then per coarser multigrid level 5 work vectors and the FP64 and FP32
+// then per coarser multigrid level 4 work vectors and the FP64 and FP32
 // inverse diagonals (8 bytes per entry each, so either precision fits).
 size_t solve_bytes_mesh(const dg_mesh& m) {
   const size_t n = (size_t)m.n_p;
   size_t b = 9 * up256(n * sizeof(double)) + 9 * up256(n * sizeof(float)) + up256(64 * sizeof(double)) +
              up256(2 * kRedBlocks * sizeof(double));
-  for (int l = 1; l < m.mg_nlev; ++l) b += 7 * up256((size_t)m.mg[l].n * sizeof(double));
+  for (int l = 1; l < m.mg_nlev; ++l) b += 6 * up256((size_t)m.mg[l].n * sizeof(double));
   return b;
 }
 }  // namespace dgwm
@@ -587,7 +585,6 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
     v.x = w; w += bytes;
     v.b = w; w += bytes;
     v.r = w; w += bytes;
-    v.d = w; w += bytes;
     v.t = w; w += bytes;
     v.dinv64 = reinterpret_cast<double*>(w); w += bytes;
     v.dinv32 = reinterpret_cast<float*>(w); w += bytes;
@@ -647,12 +644,12 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   // preconditioner z = M^{-1} r; r32_ready: the FP32 copy of r (and its
   // scale in sc[SCL]) was already written by the residual update
   auto precond = [&](double* zz, bool r32_ready) -> int {
-    if (use_mg && !sp->mixed) return S.vcycle<double>(0, zz, S.r, S.q, S.d64, S.t64, deg, degc);
+    if (use_mg && !sp->mixed) return S.vcycle<double>(0, zz, S.r, S.q, S.t64, deg, degc);
     if (!use_mg && !sp->mixed) return S.cheb<double>(zz, S.r, S.d64, S.t64, S.dinv, deg, lmin, lmax);
     // normalised FP32 copy of r (||r||^2 is in sc[RR])
     if (!r32_ready)
       hipLaunchKernelGGL(k_to_f32, dim3(S.grid), dim3(256), 0, S.s, S.r32, S.r, S.n, sc + RR, sc + SCL);
-    if (use_mg) return S.vcycle<float>(0, S.x32, S.r32, S.rr32, S.d32, S.t32, deg, degc);
+    if (use_mg) return S.vcycle<float>(0, S.x32, S.r32, S.rr32, S.t32, deg, degc);
     if (sp->max_inner == 0) {
       int e = S.cheb<float>(S.x32, S.r32, S.d32, S.t32, S.dinv32, deg, lmin, lmax);
       if (e) return e;
