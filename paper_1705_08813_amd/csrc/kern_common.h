@@ -39,7 +39,7 @@ __device__ __forceinline__ int64_t enr_index(const MeshDev& M, int ex, int ey, i
   if (ey == 0 && M.lower_slot >= 0) slot = M.lower_slot;
   else if (ey == M.ny - 1 && M.upper_slot >= 0) slot = M.upper_slot;
   if (slot < 0) return -1;
-  return ex + (int64_t)M.nx * (slot + (int64_t)M.nslots * ez);
+  return ex + M.nx * (slot + M.nslots * ez);  // below 2^31 like the cell count
 }
 
 // Apply a 1-D matrix along direction DIR (0 = x fastest) to `ncomp` stacked

@@ -65,6 +65,7 @@ struct FaceNb {
   int nidx1;       // neighbour's ey (for its height)
 };
 
+// (cell counts stay below 2^31, checked at set-up)
 __device__ __forceinline__ FaceNb face_nb(const MeshDev& M, int ex, int ey, int ez, int D, int S) {
   const int nmax = D == 0 ? M.nx : (D == 1 ? M.ny : M.nz);
   int j = (D == 0 ? ex : (D == 1 ? ey : ez)) + (S ? 1 : -1);
@@ -72,10 +73,10 @@ __device__ __forceinline__ FaceNb face_nb(const MeshDev& M, int ex, int ey, int 
   f.wall = false;
   if (j < 0 || j >= nmax) {
     if (D == 1 && !M.fully_periodic) f.wall = true;
-    j = (j + nmax) % nmax;
+    j += j < 0 ? nmax : -nmax;
   }
   const int n0 = D == 0 ? j : ex, n1 = D == 1 ? j : ey, n2 = D == 2 ? j : ez;
-  f.enb = n0 + (int64_t)M.nx * (n1 + (int64_t)M.ny * n2);
+  f.enb = n0 + M.nx * (n1 + M.ny * n2);
   f.enr_nb = f.wall ? -1 : enr_index(M, n0, n1, n2);
   f.nidx1 = n1;
   return f;
@@ -144,10 +145,8 @@ __device__ __forceinline__ void nb_store(const MeshDev& M, const NbLines<T, NP>&
 #pragma unroll
         for (int l = 0; l < NP; ++l) der += T(S ? tb.nd0[l] : tb.nd1[l]) * L.x[it][l];
         val = S ? L.x[it][0] : L.x[it][NP - 1];
-        if (!REF) {  // affine cells: physical normal derivative
-          const T hdn = D == 0 ? T(M.hx) : (D == 1 ? T(M.hy[nb.nidx1]) : T(M.hz));
-          der /= hdn;
-        }
+        if (!REF)  // affine cells: physical normal derivative
+          der *= D == 0 ? T(1) / T(M.hx) : (D == 1 ? T(1) / T(M.hy[nb.nidx1]) : T(1) / T(M.hz));
       }
       s_nl[((f * 3 + c) * 2 + 0) * NP2 + k] = val;
       s_nl[((f * 3 + c) * 2 + 1) * NP2 + k] = der;
@@ -198,7 +197,7 @@ __device__ __forceinline__ void load_face_tab(const double* tab, T* s_tab) {
 template <typename T, int NP, int NQ, int NQY, bool ENR, int D>
 __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, const T* s_nl, const T* s_nut, T* s_r,
                                               T* s_face, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
-                                              T hy, T hz, T rt[3]) {
+                                              T hy, T hz, T ihx, T ihy, T ihz, T rt[3]) {
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr int T1 = D == 0 ? 1 : 0;
   constexpr int T2 = D == 2 ? 1 : 2;
@@ -221,13 +220,16 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   T* B1 = TR;                          // [s][test 0..6][q1][i2]
   T* RB = s_face;                      // [s][c][value|normal][NP2]
 
-  const T hown[3] = {hx, hy, hz};
+  const T hown[3] = {hx, hy, hz}, ihown[3] = {ihx, ihy, ihz};
   const T hd = hown[D], ht1 = hown[T1], ht2 = hown[T2];
-  const T ihd = T(1) / hd, iht1 = T(1) / ht1, iht2 = T(1) / ht2;
+  const T ihd = ihown[D], iht1 = ihown[T1], iht2 = ihown[T2];
   const FaceNb nb0 = face_nb(M, ex, ey, ez, D, 0), nb1 = face_nb(M, ex, ey, ez, D, 1);
+  // tau = pen max(1/h-, 1/h+) = pen / min(h-, h+)
   auto tau_of = [&](const FaceNb& nb) {
-    const T ihn = (D == 1) ? T(1) / T(M.hy[nb.nidx1]) : ihd;
-    return nb.wall ? T(M.pen * M.wall_mult) * ihd : T(M.pen) * (ihd > ihn ? ihd : ihn);
+    if (nb.wall) return T(M.pen * M.wall_mult) * ihd;
+    if (D != 1) return T(M.pen) * ihd;
+    const T hn = T(M.hy[nb.nidx1]);
+    return T(M.pen) / (hd < hn ? hd : hn);
   };
   const T tau0 = tau_of(nb0), tau1 = tau_of(nb1);
   const bool wall0 = nb0.wall, wall1 = nb1.wall;
@@ -974,17 +976,20 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 0>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+                                           iz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 1>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+                                           iz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 2>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, rt);
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+                                           iz, rt);
 
   for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
   if (ENR) {
