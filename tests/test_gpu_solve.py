@@ -70,6 +70,23 @@ def test_solve_zero_rhs_and_iteration_cap():
     with pytest.raises(DgError) as ei:
         mesh.solve_poisson(b, sp=mesh.solve_params(max_outer=2))
     assert ei.value.code == -5
+    with pytest.raises(DgError) as ei:
+        mesh.solve_poisson(b, sp=mesh.solve_params(coarse_degree=-1))
+    assert ei.value.code == -1
+
+
+def test_coarse_degree_zero_means_fine_degree():
+    # coarse_degree = 0 smooths the coarser levels with cheb_degree: the same
+    # launches, so the same bits as naming that degree explicitly
+    cfg = MG_CASES["k3_stretched"]
+    mesh = Mesh(cfg)
+    b = torch.tensor(np.random.default_rng(12).uniform(-1, 1, cfg.n_p), device="cuda")
+    x0, s0 = mesh.solve_poisson(b, sp=mesh.solve_params(cheb_degree=4, coarse_degree=0))
+    x1, s1 = mesh.solve_poisson(b, sp=mesh.solve_params(cheb_degree=4, coarse_degree=4))
+    x2, s2 = mesh.solve_poisson(b, sp=mesh.solve_params(cheb_degree=4, coarse_degree=2))
+    torch.cuda.synchronize()
+    assert torch.equal(x0, x1) and s0.outer_its == s1.outer_its
+    assert s2.rel_resid <= 1e-10 and not torch.equal(x0, x2)
 
 
 MG_CASES = {
