@@ -101,9 +101,13 @@ __device__ __forceinline__ void sweep(const T* __restrict__ in, int IS, T* __res
 // straight-line code.
 // tofs rotates the thread-to-line assignment, so that independent sweeps of
 // one phase fill the threads a previous sweep left idle.
-template <int DIR, int I0, int I1, int I2, int MO, bool TR, bool ADD, typename MAT, int NT = 256, typename T>
+// With MEM the coefficients are read instead from mp (the same matrix,
+// row-major, in device memory): in FP64 a literal costs two scalar moves per
+// use, while one wide scalar load brings eight coefficients.
+template <int DIR, int I0, int I1, int I2, int MO, bool TR, bool ADD, typename MAT, int NT = 256, bool MEM = false,
+          typename T>
 __device__ __forceinline__ void sweep_c(const T* __restrict__ in, int IS, T* __restrict__ out, int OS, T scale,
-                                        int ncomp, int tofs = 0) {
+                                        int ncomp, int tofs = 0, const double* __restrict__ mp = nullptr) {
   constexpr int NI = DIR == 0 ? I0 : (DIR == 1 ? I1 : I2);
   constexpr int O0 = DIR == 0 ? MO : I0;
   constexpr int O1 = DIR == 1 ? MO : I1;
@@ -136,7 +140,8 @@ __device__ __forceinline__ void sweep_c(const T* __restrict__ in, int IS, T* __r
     for (int m = 0; m < MO; ++m) {
       T s = 0;
 #pragma unroll
-      for (int n = 0; n < NI; ++n) s += T(TR ? MAT::at(n, m) : MAT::at(m, n)) * v[n];
+      for (int n = 0; n < NI; ++n)
+        s += T(MEM ? mp[TR ? n * MO + m : m * NI + n] : (TR ? MAT::at(n, m) : MAT::at(m, n))) * v[n];
       if (ADD)
         dst[m * SOUT] += scale * s;
       else
@@ -148,8 +153,9 @@ __device__ __forceinline__ void sweep_c(const T* __restrict__ in, int IS, T* __r
 // In-place square sweep (MO = NI): every thread reads its whole line into
 // registers before writing it back, and lines are disjoint, so input and
 // output may be the same array (no __restrict__ here on purpose).
-template <int DIR, int I0, int I1, int I2, bool TR, typename MAT, int NT = 256, typename T>
-__device__ __forceinline__ void sweep_c_inplace(T* a, int IS, T scale, int ncomp, int tofs = 0) {
+template <int DIR, int I0, int I1, int I2, bool TR, typename MAT, int NT = 256, bool MEM = false, typename T>
+__device__ __forceinline__ void sweep_c_inplace(T* a, int IS, T scale, int ncomp, int tofs = 0,
+                                                const double* __restrict__ mp = nullptr) {
   constexpr int NI = DIR == 0 ? I0 : (DIR == 1 ? I1 : I2);
   constexpr int P0 = DIR == 0 ? I1 : I0;
   constexpr int P1 = DIR == 2 ? I1 : I2;
@@ -169,7 +175,8 @@ __device__ __forceinline__ void sweep_c_inplace(T* a, int IS, T scale, int ncomp
     for (int m = 0; m < NI; ++m) {
       T s = 0;
 #pragma unroll
-      for (int n = 0; n < NI; ++n) s += T(TR ? MAT::at(n, m) : MAT::at(m, n)) * v[n];
+      for (int n = 0; n < NI; ++n)
+        s += T(MEM ? mp[TR ? n * NI + m : m * NI + n] : (TR ? MAT::at(n, m) : MAT::at(m, n))) * v[n];
       w[m] = scale * s;
     }
 #pragma unroll

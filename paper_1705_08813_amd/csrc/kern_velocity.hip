@@ -833,6 +833,13 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   using Dy = ct::MatD<NP, NQY>;
   constexpr auto& tbx = ct::tab<NP, NQ>;
   constexpr auto& tby = ct::tab<NP, NQY>;
+  // FP64 sweeps read the same tables from the mesh's table block (see sweep_c)
+  constexpr bool MEM = sizeof(T) == 8;
+  constexpr TabLayout TL = tab_layout(NP, NQ, NQY);
+  const double* mSx = tab + TL.S;
+  const double* mDx = tab + TL.D;
+  const double* mSy = tab + (ENR ? TL.Sy : TL.S);
+  const double* mDy = tab + (ENR ? TL.Dy : TL.D);
 
   for (int i = tid; i < 3 * NP3; i += nt) s_u[i] = u[e * 3 * NP3 + i];
   if (ENR && tid < 3) s_ut[tid] = u[M.enr_off + enr * 3 + tid];
@@ -847,20 +854,22 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   {
     T* tA = s_grad;                       // (NQ, NP, NP) x 3
     T* tB = tA + 3 * NQ * NP * NP;        // (NQ, NQY, NP) x 3
-    sweep_c<0, NP, NP, NP, NQ, false, false, Sx>(s_u, NP3, tA, NQ * NP * NP, T(1), 3);
+    sweep_c<0, NP, NP, NP, NQ, false, false, Sx, 256, MEM>(s_u, NP3, tA, NQ * NP * NP, T(1), 3, 0, mSx);
     __syncthreads();
-    sweep_c<1, NQ, NP, NP, NQY, false, false, Sy>(tA, NQ * NP * NP, tB, NQ * NQY * NP, T(1), 3);
+    sweep_c<1, NQ, NP, NP, NQY, false, false, Sy, 256, MEM>(tA, NQ * NP * NP, tB, NQ * NQY * NP, T(1), 3, 0, mSy);
     __syncthreads();
-    sweep_c<2, NQ, NQY, NP, NQ, false, false, Sx>(tB, NQ * NQY * NP, s_val, NPTS, T(1), 3);
+    sweep_c<2, NQ, NQY, NP, NQ, false, false, Sx, 256, MEM>(tB, NQ * NQY * NP, s_val, NPTS, T(1), 3, 0, mSx);
     __syncthreads();
   }
   // gradients by collocation through the Gauss points
   // (the three sweeps are independent: rotated thread assignments pack them)
   constexpr int NLG = 3 * NPTS / NQ;   // lines per x- or z-sweep (3 components)
   constexpr int NLY = 3 * NPTS / NQY;  // lines per y-sweep
-  sweep_c<0, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0);
-  sweep_c<1, NQ, NQY, NQ, NQY, false, false, Dy>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, iy, 3, NLG % 256);
-  sweep_c<2, NQ, NQY, NQ, NQ, false, false, Dx>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, iz, 3, (NLG + NLY) % 256);
+  sweep_c<0, NQ, NQY, NQ, NQ, false, false, Dx, 256, MEM>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0, mDx);
+  sweep_c<1, NQ, NQY, NQ, NQY, false, false, Dy, 256, MEM>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, iy, 3,
+                                                           NLG % 256, mDy);
+  sweep_c<2, NQ, NQY, NQ, NQ, false, false, Dx, 256, MEM>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, iz, 3,
+                                                          (NLG + NLY) % 256, mDx);
   __syncthreads();
 
   // pointwise flux G = 2 nu eps(u) - u (x) u, times the quadrature weight
@@ -927,8 +936,8 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   // integrate: W = sum_d D_d^T G_d / h_d, then transposed interpolation.
   // The x and y parts are formed in place (one phase); each z line then adds
   // its own D_z^T G_z to them and applies S_z^T directly.
-  sweep_c_inplace<0, NQ, NQY, NQ, true, Dx>(s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0);
-  sweep_c_inplace<1, NQ, NQY, NQ, true, Dy>(s_grad + 1 * NPTS, 3 * NPTS, iy, 3, NLG % 256);
+  sweep_c_inplace<0, NQ, NQY, NQ, true, Dx, 256, MEM>(s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0, mDx);
+  sweep_c_inplace<1, NQ, NQY, NQ, true, Dy, 256, MEM>(s_grad + 1 * NPTS, 3 * NPTS, iy, 3, NLG % 256, mDy);
   __syncthreads();
   {
     T* tB = s_val;                        // (NQ, NQY, NP) x 3 (u is no longer needed)
@@ -948,7 +957,7 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
       for (int m = 0; m < NQ; ++m) {
         T sacc = 0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) sacc += T(tbz.D[q][m]) * g[q];
+        for (int q = 0; q < NQ; ++q) sacc += T(MEM ? mDx[q * NQ + m] : tbz.D[q][m]) * g[q];
         w[m] += iz * sacc;
       }
       T* o = tB + c * (NQ * NQY * NP) + pq;
@@ -956,14 +965,14 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
       for (int i = 0; i < NP; ++i) {
         T sacc = 0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) sacc += T(tbz.S[q][i]) * w[q];
+        for (int q = 0; q < NQ; ++q) sacc += T(MEM ? mSx[q * NP + i] : tbz.S[q][i]) * w[q];
         o[i * NQ * NQY] = sacc;
       }
     }
     __syncthreads();
-    sweep_c<1, NQ, NQY, NP, NP, true, false, Sy>(tB, NQ * NQY * NP, tA, NQ * NP * NP, T(1), 3);
+    sweep_c<1, NQ, NQY, NP, NP, true, false, Sy, 256, MEM>(tB, NQ * NQY * NP, tA, NQ * NP * NP, T(1), 3, 0, mSy);
     __syncthreads();
-    sweep_c<0, NQ, NP, NP, NP, true, false, Sx>(tA, NQ * NP * NP, s_r, NP3, T(1), 3);
+    sweep_c<0, NQ, NP, NP, NP, true, false, Sx, 256, MEM>(tA, NQ * NP * NP, s_r, NP3, T(1), 3, 0, mSx);
     __syncthreads();
   }
 
