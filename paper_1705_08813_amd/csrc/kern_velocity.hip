@@ -125,9 +125,11 @@ __device__ __forceinline__ void nb_fetch(const MeshDev& M, const T* __restrict__
   }
 }
 
+// ihn: reciprocal size along the face normal of the neighbours across the
+// faces y = 0 and y = 1 of the cell (x and z sizes are uniform)
 template <typename T, int NP, int NQ, bool REF>
 __device__ __forceinline__ void nb_store(const MeshDev& M, const NbLines<T, NP>& L, T* s_nl, T* s_nut, int ex, int ey,
-                                         int ez) {
+                                         int ez, T ihx, T ihz, T ihy0, T ihy1) {
   using NL = NbLines<T, NP>;
   constexpr int NP2 = NL::NP2;
   constexpr auto& tb = ct::tab<NP, NQ>;
@@ -141,12 +143,18 @@ __device__ __forceinline__ void nb_store(const MeshDev& M, const NbLines<T, NP>&
       T val = 0, der = 0;
       const FaceNb nb = face_nb(M, ex, ey, ez, D, S);
       if (!nb.wall) {
-        // the neighbour's face is at xi_D = 1 - S
+        // the neighbour's face is at xi_D = 1 - S (both sums, one select:
+        // a per-lane choice of coefficients would cost a select per term)
+        T d0 = 0, d1 = 0;
 #pragma unroll
-        for (int l = 0; l < NP; ++l) der += T(S ? tb.nd0[l] : tb.nd1[l]) * L.x[it][l];
+        for (int l = 0; l < NP; ++l) {
+          d0 += T(tb.nd0[l]) * L.x[it][l];
+          d1 += T(tb.nd1[l]) * L.x[it][l];
+        }
+        der = S ? d0 : d1;
         val = S ? L.x[it][0] : L.x[it][NP - 1];
         if (!REF)  // affine cells: physical normal derivative
-          der *= D == 0 ? T(1) / T(M.hx) : (D == 1 ? T(1) / T(M.hy[nb.nidx1]) : T(1) / T(M.hz));
+          der *= D == 0 ? ihx : (D == 1 ? (S ? ihy1 : ihy0) : ihz);
       }
       s_nl[((f * 3 + c) * 2 + 0) * NP2 + k] = val;
       s_nl[((f * 3 + c) * 2 + 1) * NP2 + k] = der;
@@ -979,7 +987,11 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   // faces: neighbour layers of all six faces (one phase), then each direction
   T* s_nl = s_big;
   T* s_face = s_big + Sh::NL;
-  nb_store<T, NP, NQ, CURVED>(M, nbl, s_nl, s_nut, ex, ey, ez);
+  {
+    // neighbours across y = 0 and y = 1 (wrapped; unused on walls)
+    const int y0 = ey == 0 ? M.ny - 1 : ey - 1, y1 = ey + 1 == M.ny ? 0 : ey + 1;
+    nb_store<T, NP, NQ, CURVED>(M, nbl, s_nl, s_nut, ex, ey, ez, ix, iz, T(1) / T(M.hy[y0]), T(1) / T(M.hy[y1]));
+  }
   __syncthreads();
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 0>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
