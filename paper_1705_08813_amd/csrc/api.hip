@@ -99,7 +99,7 @@ WsLayout layout(const dg_mesh& m) {
   WsLayout L{};
   size_t o = 0;
   L.eta = o; o = up256(o + sizeof(double) * (m.P.ny + 1));
-  L.hy = o; o = up256(o + sizeof(double) * m.P.ny);
+  L.hy = o; o = up256(o + sizeof(double) * 2 * m.P.ny);  // heights, then their reciprocals
   L.tab_u = o;
   o = up256(o + sizeof(double) * (tab_layout(m.np_u, m.P.nq_u, m.P.nq_wn).size + m.P.nq_u + m.P.nq_wn));
   L.tab_p = o;
@@ -113,7 +113,7 @@ WsLayout layout(const dg_mesh& m) {
   L.tauF = o; o = up256(o + sizeof(double) * (m.curved ? 6 * (size_t)m.ncell : 0));
   L.wdist = o; o = up256(o + sizeof(double) * (m.curved ? 2 * (size_t)(m.P.nx + 1) : 0));
   for (int l = 1; l < m.mg_nlev; ++l) {
-    L.mg_hy[l] = o; o = up256(o + sizeof(double) * m.mg[l].ny);
+    L.mg_hy[l] = o; o = up256(o + sizeof(double) * 2 * m.mg[l].ny);
     L.mg_diag[l] = o; o = up256(o + sizeof(double) * m.mg[l].n);
     L.mg_diag32[l] = o; o = up256(o + sizeof(float) * m.mg[l].n);
   }
@@ -210,12 +210,15 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
 
   const dg_mesh_params& P = m->P;
   // wall-normal vertices: tanh grading (paper Sec. 5.1)
-  std::vector<double> eta(P.ny + 1), hy(P.ny);
+  std::vector<double> eta(P.ny + 1), hy(2 * P.ny);  // heights, then their reciprocals
   for (int j = 0; j <= P.ny; ++j) {
     const double t = 2.0 * j / P.ny - 1.0;
     eta[j] = P.gamma > 0 ? std::tanh(P.gamma * t) / std::tanh(P.gamma) : t;
   }
-  for (int j = 0; j < P.ny; ++j) hy[j] = eta[j + 1] - eta[j];
+  for (int j = 0; j < P.ny; ++j) {
+    hy[j] = eta[j + 1] - eta[j];
+    hy[P.ny + j] = 1.0 / hy[j];
+  }
   const TabLayout Lu = tab_layout(m->np_u, P.nq_u, P.nq_wn);
   std::vector<double> tu(Lu.size + P.nq_u + P.nq_wn), tp(tab_layout(m->np_p, P.nq_p, P.nq_p).size + poi_ops(m->np_p).size);
   fill_tables(m->np_u, P.nq_u, P.nq_wn, tu.data());

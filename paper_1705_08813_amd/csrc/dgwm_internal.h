@@ -108,7 +108,7 @@ struct MgLevel {
   int cx = 0, cy = 0, cz = 0;         // coarsened from level l-1 along x, y, z
   int64_t ncell = 0, n = 0;
   double hx = 0, hz = 0;
-  double* hy = nullptr;               // ny cell heights (device)
+  double* hy = nullptr;               // ny cell heights, then their ny reciprocals (device)
   double* diag = nullptr;             // Jacobi diagonal (device, FP64 and FP32)
   float* diag32 = nullptr;
   double lam = 0.0;                   // cached Lanczos estimate of lmax(D^{-1} A)
@@ -148,7 +148,7 @@ struct dg_mesh {
   double* psi;            // [enr][psi_pts][4]: psi, dpsi/dx, dpsi/dy, dpsi/dz
   double* diag;           // Poisson diagonal (FP64)
   float* diag32;          // Poisson diagonal (FP32 copy)
-  double* hy;             // ny cell heights
+  double* hy;             // ny cell heights, then their ny reciprocals
   double lam_max = 0.0;   // cached largest eigenvalue estimate of D^{-1} A (solver)
   // curved lower wall (wall_amp != 0)
   int curved = 0;

@@ -16,6 +16,8 @@ struct MeshDev {
   int lower_slot, upper_slot, nslots;  // enriched-layer slots (-1: wall not enriched)
   double hx, hz;
   const double* hy;   // ny cell heights
+  double ihx, ihz;    // 1 / hx, 1 / hz
+  const double* ihy;  // ny reciprocal cell heights
   const double* tab;  // 1-D tables (tab_layout)
   const double* psi;  // [enr][psi_pts][4]
   int psi_pts;

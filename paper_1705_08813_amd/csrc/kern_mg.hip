@@ -625,9 +625,12 @@ int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hi
       for (int j = 0; j <= c.ny; ++j) e2[j] = eta[2 * j];
       eta.swap(e2);
     }
-    hys[l].resize(c.ny);
-    for (int j = 0; j < c.ny; ++j) hys[l][j] = eta[j + 1] - eta[j];
-    rc = check_hip(hipMemcpyAsync(m->mg[l].hy, hys[l].data(), sizeof(double) * c.ny, hipMemcpyHostToDevice, s),
+    hys[l].resize(2 * c.ny);  // heights, then their reciprocals
+    for (int j = 0; j < c.ny; ++j) {
+      hys[l][j] = eta[j + 1] - eta[j];
+      hys[l][c.ny + j] = 1.0 / hys[l][j];
+    }
+    rc = check_hip(hipMemcpyAsync(m->mg[l].hy, hys[l].data(), sizeof(double) * 2 * c.ny, hipMemcpyHostToDevice, s),
                    "level heights");
     if (!rc) rc = launch_poisson_diag_level(m, l, s);
   }

@@ -151,8 +151,9 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
     h[0] = T(M.hx);
     h[1] = T(M.hy[ey]);
     h[2] = T(M.hz);
-#pragma unroll
-    for (int D = 0; D < 3; ++D) rh[D] = T(1) / h[D];
+    rh[0] = T(M.ihx);
+    rh[1] = T(M.ihy[ey]);
+    rh[2] = T(M.ihz);
     const int bx = pencil_base<NP>(0, a, b);
     const int64_t o = e * NP3 + bx;
     if (KIND != kPlain) {
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
           v = S ? q[0] : q[NP - 1];
           if (D == 1) {
             const int yn = S ? (ey + 1 == M.ny ? 0 : ey + 1) : (ey == 0 ? M.ny - 1 : ey - 1);
-            rn = T(1) / T(M.hy[yn]);
+            rn = T(M.ihy[yn]);
           }
           d *= rn;
         }
@@ -428,6 +429,9 @@ MeshDev make_meshdev_p(const dg_mesh* m, int l = 0) {
   M.hx = lv ? lv->hx : m->hx;
   M.hz = lv ? lv->hz : m->hz;
   M.hy = lv ? lv->hy : m->hy;
+  M.ihy = M.hy + M.ny;
+  M.ihx = 1.0 / M.hx;
+  M.ihz = 1.0 / M.hz;
   M.tab = m->tab_p;
   M.ops_off = tab_layout(m->np_p, m->P.nq_p, m->P.nq_p).size;
   M.pen = m->P.ip_factor_p * (m->P.k_p + 1.0) * (m->P.k_p + 1.0);

@@ -229,15 +229,15 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   T* RB = s_face;                      // [s][c][value|normal][NP2]
 
   const T hown[3] = {hx, hy, hz}, ihown[3] = {ihx, ihy, ihz};
-  const T hd = hown[D], ht1 = hown[T1], ht2 = hown[T2];
+  const T ht1 = hown[T1], ht2 = hown[T2];
   const T ihd = ihown[D], iht1 = ihown[T1], iht2 = ihown[T2];
   const FaceNb nb0 = face_nb(M, ex, ey, ez, D, 0), nb1 = face_nb(M, ex, ey, ez, D, 1);
-  // tau = pen max(1/h-, 1/h+) = pen / min(h-, h+)
+  // tau = pen max(1/h-, 1/h+)
   auto tau_of = [&](const FaceNb& nb) {
     if (nb.wall) return T(M.pen * M.wall_mult) * ihd;
     if (D != 1) return T(M.pen) * ihd;
-    const T hn = T(M.hy[nb.nidx1]);
-    return T(M.pen) / (hd < hn ? hd : hn);
+    const T ihn = T(M.ihy[nb.nidx1]);
+    return T(M.pen) * (ihd > ihn ? ihd : ihn);
   };
   const T tau0 = tau_of(nb0), tau1 = tau_of(nb1);
   const bool wall0 = nb0.wall, wall1 = nb1.wall;
@@ -830,7 +830,7 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   const int64_t e = ex + (int64_t)M.nx * (ey + (int64_t)M.ny * ez);
   const T hx = T(M.hx), hz = T(M.hz), hy = T(M.hy[ey]);
   // sweeps produce physical derivatives on affine cells, reference ones on curved cells
-  const T ix = CURVED ? T(1) : T(1) / hx, iy = CURVED ? T(1) : T(1) / hy, iz = CURVED ? T(1) : T(1) / hz;
+  const T ix = CURVED ? T(1) : T(M.ihx), iy = CURVED ? T(1) : T(M.ihy[ey]), iz = CURVED ? T(1) : T(M.ihz);
 
   const double* tab = M.tab;
   // volume sweep matrices: compile-time tables (x and z use the NQ rule, y
@@ -990,7 +990,7 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   {
     // neighbours across y = 0 and y = 1 (wrapped; unused on walls)
     const int y0 = ey == 0 ? M.ny - 1 : ey - 1, y1 = ey + 1 == M.ny ? 0 : ey + 1;
-    nb_store<T, NP, NQ, CURVED>(M, nbl, s_nl, s_nut, ex, ey, ez, ix, iz, T(1) / T(M.hy[y0]), T(1) / T(M.hy[y1]));
+    nb_store<T, NP, NQ, CURVED>(M, nbl, s_nl, s_nut, ex, ey, ez, ix, iz, T(M.ihy[y0]), T(M.ihy[y1]));
   }
   __syncthreads();
   if (CURVED)
@@ -1098,6 +1098,9 @@ MeshDev make_meshdev_u(const dg_mesh* m) {
   M.hx = m->hx;
   M.hz = m->hz;
   M.hy = m->hy;
+  M.ihy = m->hy + m->P.ny;
+  M.ihx = 1.0 / m->hx;
+  M.ihz = 1.0 / m->hz;
   M.tab = m->tab_u;
   M.psi = m->psi;
   M.psi_pts = m->psi_pts;
