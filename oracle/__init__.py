@@ -66,6 +66,9 @@ def lib():
         L.orc_poisson_apply.argtypes = [P, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
         L.orc_poisson_diag.argtypes = [P, _I64, ctypes.c_int64, _D]
         L.orc_psi_point.argtypes = [P, _D, ctypes.c_int64, _D, _D]
+        L.orc_velocity_residual_nodal.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
+        L.orc_psi_point_nodal.argtypes = [P, _D, ctypes.c_int64, _D, _D]
+        L.orc_wall_shear_nodes.argtypes = [P, _D, _D, _D, _D]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
@@ -174,6 +177,60 @@ def velocity_residual(cfg, u, tau, cells=None, absmode=False):
     if rc:
         raise RuntimeError(f"orc_velocity_residual failed: {rc}")
     return r
+
+
+def _tau_nodes(cfg, tau_nodes):
+    p = params(cfg)
+    t = _f64(tau_nodes).reshape(-1)
+    if t.size != 2 * p.nz * p.nx:
+        raise ValueError(f"tau_nodes has {t.size} entries, expected {2 * p.nz * p.nx}")
+    return t
+
+
+def velocity_residual_nodal(cfg, u, tau_nodes, cells=None, absmode=False):
+    """Residual with the nodal wall shear stress field tau_nodes [wall][nz][nx]
+    (Sec. 3.2: bilinear tau_w,h, grad psi with the grad tau_w term)."""
+    p = params(cfg)
+    u = _f64(u)
+    n = num_dofs(cfg, 0)
+    if u.size != n:
+        raise ValueError(f"u has {u.size} entries, expected {n}")
+    t = _tau_nodes(cfg, tau_nodes)
+    cells = _cells(cfg, cells)
+    r = np.zeros(n)
+    rc = lib().orc_velocity_residual_nodal(ctypes.byref(p), _ptr(u), _ptr(t), cells.ctypes.data_as(_I64),
+                                           cells.size, _ptr(r), int(absmode))
+    if rc:
+        raise RuntimeError(f"orc_velocity_residual_nodal failed: {rc}")
+    return r
+
+
+def psi_point_nodal(cfg, tau_nodes, e, xi):
+    p = params(cfg)
+    t = _tau_nodes(cfg, tau_nodes)
+    xi = _f64(xi)
+    out = np.zeros(4)
+    rc = lib().orc_psi_point_nodal(ctypes.byref(p), _ptr(t), int(e), _ptr(xi), _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_psi_point_nodal failed: {rc}")
+    return out
+
+
+def wall_shear_nodes(cfg, u, tau=None, tau_nodes=None):
+    """Nodal wall shear stress [wall][nz][nx] of the velocity u (Sec. 3.2),
+    with psi from the per-point tau or, when given, the nodal tau_nodes."""
+    p = params(cfg)
+    u = _f64(u)
+    if u.size != num_dofs(cfg, 0):
+        raise ValueError("u has the wrong size")
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    out = np.zeros(2 * p.nz * p.nx)
+    rc = lib().orc_wall_shear_nodes(ctypes.byref(p), _ptr(u), _ptr(t) if t is not None else None,
+                                    _ptr(tn) if tn is not None else None, _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_wall_shear_nodes failed: {rc}")
+    return out.reshape(2, p.nz, p.nx)
 
 
 def poisson_apply(cfg, x, cells=None, absmode=False):

@@ -226,6 +226,7 @@ typedef struct {
   double qwn[ORC_MAXN], wwn[ORC_MAXN];
   double qp[ORC_MAXN], wp[ORC_MAXN];
   const double *tau;  /* wall shear stress per wall-face quadrature point */
+  const double *tau_nodes; /* or: nodal wall shear stress [wall][nz][nx] (Sec. 3.2, m = 1) */
 } ctx;
 
 /* Wall-normal vertex coordinate, Sec. 5.1: f(t) = tanh(gamma(2t-1))/tanh(gamma). */
@@ -413,21 +414,41 @@ static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double J
       }
   double gyh[3];
   for (int d = 0; d < 3; ++d) gyh[d] = gr[0] * Ji[0][d] + gr[1] * Ji[1][d] + gr[2] * Ji[2][d];
-  /* nearest Gauss column of the velocity rule */
-  int nq = C->P.nq_u, qx = 0, qz = 0;
-  for (int q = 1; q < nq; ++q) {
-    if (fabs(xi[0] - C->qu[q]) < fabs(xi[0] - C->qu[qx])) qx = q;
-    if (fabs(xi[2] - C->qu[q]) < fabs(xi[2] - C->qu[qz])) qz = q;
+  double tw, gtw[3] = {0, 0, 0};
+  if (C->tau_nodes) {
+    /* Sec. 3.2: tau_w,h = sum_B N_B tau_w,B with the bilinear (m = 1) hat
+     * functions of the wall vertices, extended constant along the wall
+     * normal; x and z are affine in the reference coordinates */
+    double hx = C->P.Lx / C->P.nx, hz = C->P.Lz / C->P.nz;
+    tw = 0;
+    for (int c = 0; c < 2; ++c)
+      for (int a = 0; a < 2; ++a) {
+        int jx = (ex + a) % C->P.nx, jz = (ez + c) % C->P.nz;
+        double tb = C->tau_nodes[((int64_t)w * C->P.nz + jz) * C->P.nx + jx];
+        double nxa = a ? xi[0] : 1 - xi[0], nzc = c ? xi[2] : 1 - xi[2];
+        tw += nxa * nzc * tb;
+        gtw[0] += (a ? 1.0 : -1.0) / hx * nzc * tb;
+        gtw[2] += nxa * (c ? 1.0 : -1.0) / hz * tb;
+      }
+  } else {
+    /* nearest Gauss column of the velocity rule */
+    int nq = C->P.nq_u, qx = 0, qz = 0;
+    for (int q = 1; q < nq; ++q) {
+      if (fabs(xi[0] - C->qu[q]) < fabs(xi[0] - C->qu[qx])) qx = q;
+      if (fabs(xi[2] - C->qu[q]) < fabs(xi[2] - C->qu[qz])) qz = q;
+    }
+    int64_t ti = (((int64_t)w * C->P.nz + ez) * C->P.nx + ex) * nq * nq + (int64_t)qz * nq + qx;
+    tw = C->tau[ti];
   }
-  int64_t ti = (((int64_t)w * C->P.nz + ez) * C->P.nx + ex) * nq * nq + (int64_t)qz * nq + qx;
-  double st = sqrt(C->tau[ti]) / C->P.nu;
+  double st = sqrt(tw) / C->P.nu;
   double U, dU;
   if (C->P.psi_kind == 1)
     orc_vandriest(yh * st, C->P.kappa, C->P.A_plus, &U, &dU);
   else
     orc_spalding(yh * st, C->P.kappa, C->P.B, &U, &dU);
   out->psi = U;
-  for (int d = 0; d < 3; ++d) out->g[d] = dU * st * gyh[d];
+  /* grad y+ = sqrt(tau)/nu grad y_h + y_h / (2 nu sqrt(tau)) grad tau */
+  for (int d = 0; d < 3; ++d) out->g[d] = dU * (st * gyh[d] + yh / (2.0 * C->P.nu * sqrt(tw)) * gtw[d]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -497,6 +518,7 @@ static void eval_vel(const ctx *C, const double *u, int64_t e, const double xi[3
 /* ------------------------------------------------------------------------ */
 
 static int ctx_init(ctx *C, const orc_params *P, const double *tau) {
+  /* (tau_nodes is set by the callers that take nodal values) */
   memset(C, 0, sizeof(*C));
   C->P = *P;
   if (P->nx < 1 || P->ny < 1 || P->nz < 1) return -1;
@@ -708,11 +730,12 @@ static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int ab
   }
 }
 
-int orc_velocity_residual(const orc_params *P, const double *u, const double *tau_w,
-                          const int64_t *cells, int64_t ncells, double *r, int absmode) {
+static int velocity_residual(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
+                             const int64_t *cells, int64_t ncells, double *r, int absmode) {
   ctx C;
   if (ctx_init(&C, P, tau_w)) return -1;
-  if (C.nenr > 0 && !tau_w) { ctx_free(&C); return -2; }
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   int n = C.npu, np3 = n * n * n;
   int err = 0;
 #pragma omp parallel
@@ -730,6 +753,16 @@ int orc_velocity_residual(const orc_params *P, const double *u, const double *ta
   }
   ctx_free(&C);
   return err;
+}
+
+int orc_velocity_residual(const orc_params *P, const double *u, const double *tau_w,
+                          const int64_t *cells, int64_t ncells, double *r, int absmode) {
+  return velocity_residual(P, u, tau_w, NULL, cells, ncells, r, absmode);
+}
+
+int orc_velocity_residual_nodal(const orc_params *P, const double *u, const double *tau_nodes,
+                                const int64_t *cells, int64_t ncells, double *r, int absmode) {
+  return velocity_residual(P, u, NULL, tau_nodes, cells, ncells, r, absmode);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -892,6 +925,81 @@ int orc_psi_point(const orc_params *P, const double *tau_w, int64_t e, const dou
   eval_psi(&C, e, xi, Ji, &pt);
   out4[0] = pt.psi;
   out4[1] = pt.g[0]; out4[2] = pt.g[1]; out4[3] = pt.g[2];
+  ctx_free(&C);
+  return 0;
+}
+
+/* psi and grad psi with a nodal wall shear stress field tau_nodes
+ * [wall][nz][nx] (Sec. 3.2): tau_w,h bilinear between the wall vertices, grad
+ * psi with the grad tau_w term of the chain rule. */
+int orc_psi_point_nodal(const orc_params *P, const double *tau_nodes, int64_t e, const double *xi, double *out4) {
+  ctx C;
+  if (ctx_init(&C, P, NULL)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (e < 0 || e >= C.ncell || C.enr[e] < 0) { ctx_free(&C); return -2; }
+  double X[3], J[3][3], Ji[3][3];
+  cell_map(&C, e, xi, X, J);
+  inv3(J, Ji);
+  psi_pt pt;
+  eval_psi(&C, e, xi, Ji, &pt);
+  out4[0] = pt.psi;
+  out4[1] = pt.g[0]; out4[2] = pt.g[1]; out4[3] = pt.g[2];
+  ctx_free(&C);
+  return 0;
+}
+
+/* Nodal wall shear stress of both walls (Sec. 3.2):
+ *   tau_w,B = || int_{wall} N_B tau_w dA || / int_{wall} N_B dA,
+ * tau_w = nu (grad u_h) n with the outward normal n = -e_y (lower wall) or
+ * +e_y (upper wall) and u_h the full (enriched) velocity, whose psi comes
+ * from the current tau field (tau_w per point, or tau_nodes when given);
+ * N_B the bilinear hat function of wall vertex B, both integrals by the
+ * velocity rule's Gauss points on the wall faces.  Flat walls only.
+ * out: [wall][nz][nx]. */
+int orc_wall_shear_nodes(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
+                         double *out) {
+  ctx C;
+  if (P->fully_periodic || P->wall_amp != 0.0) return -3;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  int nx = P->nx, nz = P->nz, nq = P->nq_u, n = C.npu, np3 = n * n * n;
+  double hx = P->Lx / nx, hz = P->Lz / nz;
+  double *num = (double *)calloc((size_t)2 * nz * nx * 3, sizeof(double));
+  double *den = (double *)calloc((size_t)2 * nz * nx, sizeof(double));
+  double *bv = (double *)malloc(sizeof(double) * np3 * 4);
+  double(*bg)[3] = (double(*)[3])(bv + np3);
+  for (int w = 0; w < 2; ++w) {
+    int ey = w ? P->ny - 1 : 0;
+    double ny_out = w ? 1.0 : -1.0;
+    for (int ez = 0; ez < nz; ++ez)
+      for (int ex = 0; ex < nx; ++ex) {
+        int64_t e = ex + (int64_t)nx * (ey + (int64_t)P->ny * ez);
+        for (int qz = 0; qz < nq; ++qz)
+          for (int qx = 0; qx < nq; ++qx) {
+            double xi[3] = {C.qu[qx], w ? 1.0 : 0.0, C.qu[qz]};
+            double X[3], J[3][3], Ji[3][3];
+            cell_map(&C, e, xi, X, J);
+            inv3(J, Ji);
+            vel_pt vp;
+            eval_vel(&C, u, e, xi, Ji, 0, &vp, bv, bg);
+            double dA = C.wu[qx] * C.wu[qz] * hx * hz;
+            for (int c = 0; c < 2; ++c)
+              for (int a = 0; a < 2; ++a) {
+                double N = (a ? xi[0] : 1 - xi[0]) * (c ? xi[2] : 1 - xi[2]);
+                int64_t node = ((int64_t)w * nz + (ez + c) % nz) * nx + (ex + a) % nx;
+                for (int i = 0; i < 3; ++i) num[node * 3 + i] += N * dA * P->nu * vp.g[i][1] * ny_out;
+                den[node] += N * dA;
+              }
+          }
+      }
+  }
+  for (int64_t b = 0; b < (int64_t)2 * nz * nx; ++b)
+    out[b] = sqrt(num[b * 3] * num[b * 3] + num[b * 3 + 1] * num[b * 3 + 1] + num[b * 3 + 2] * num[b * 3 + 2]) /
+             den[b];
+  free(num);
+  free(den);
+  free(bv);
   ctx_free(&C);
   return 0;
 }
