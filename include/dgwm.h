@@ -116,6 +116,35 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
  * enrichment space are updated once per time step).  Enqueued on `stream`. */
 int dg_update_wall_shear(dg_mesh* mesh, const double* tau_w_dev, void* stream);
 
+/* Nodal wall shear stress of both walls from the FP64 velocity u (paper
+ * Sec. 3.2: the wall shear stress is averaged onto the wall nodes with the
+ * bilinear (m = 1) hat functions N_B of the wall vertices):
+ *   tau_w,B = || int_wall N_B nu (grad u_h) n dA || / int_wall N_B dA,
+ * n the outward unit normal (-e_y lower wall, +e_y upper wall), u_h the full
+ * velocity including psi u~ with the mesh's current psi, both integrals by
+ * the velocity rule's nq_u x nq_u Gauss points of each wall face.
+ *   u:         device, dg_num_dofs(mesh, 0) doubles.
+ *   tau_nodes: device output, 2*nz*nx doubles in the layout
+ *              [wall w (0 lower, 1 upper)][jz][jx], vertex (jx Lx/nx, jz Lz/nz)
+ *              of the periodic wall grid; fully overwritten.
+ * Deterministic (fixed summation order).  Uses a scratch area of the mesh
+ * workspace, so two calls on one handle must not overlap.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall or a fully
+ *   periodic mesh: flat no-slip walls only), DG_ERR_HIP. */
+int dg_wall_shear_nodes(const dg_mesh* mesh, const double* u, double* tau_nodes, void* stream);
+
+/* Replace the wall shear stress by a nodal field (device, [wall][jz][jx] as
+ * dg_wall_shear_nodes writes it, all > 0 and finite) and recompute psi and
+ * grad psi in FP64 (paper Sec. 3.2): tau_w,h is the bilinear interpolation of
+ * the nodal values along the wall, constant along the wall normal, and
+ * grad y+ = sqrt(tau_w)/nu grad y_h + y_h / (2 nu sqrt(tau_w)) grad tau_w,h.
+ * The values are copied; psi entries of points where tau_w,h is not positive
+ * and finite become NaN.  The mesh keeps this field until the next
+ * dg_update_wall_shear (per-point field) or dg_update_wall_shear_nodes call.
+ * Flat no-slip walls only (DG_ERR_UNSUPPORTED otherwise).  Enqueued on
+ * `stream`. */
+int dg_update_wall_shear_nodes(dg_mesh* mesh, const double* tau_nodes, void* stream);
+
 /* Number of entries of the velocity (field 0, polynomial + enrichment) or
  * pressure (field 1) vector; negative on error. */
 int64_t dg_num_dofs(const dg_mesh* mesh, int field);

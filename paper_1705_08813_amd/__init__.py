@@ -95,11 +95,44 @@ class Mesh:
         _lib.check(_lib.lib().dg_poisson_diagonal(self.handle, _dptr(d), _stream_ptr(stream)))
         return d
 
-    def update_wall_shear(self, tau_dev, stream=None):
+    def _check_f64(self, t, n, name):
         import torch
-        if tau_dev.dtype != torch.float64 or tau_dev.device != self.device or not tau_dev.is_contiguous():
-            raise ValueError("tau must be a contiguous float64 tensor on the mesh device")
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \
+                or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+
+    @property
+    def n_tau(self):
+        p = self.params
+        return 2 * p.nz * p.nx * p.nq_u * p.nq_u
+
+    @property
+    def n_wall_nodes(self):
+        return 2 * self.params.nz * self.params.nx
+
+    def update_wall_shear(self, tau_dev, stream=None):
+        """Per-point tau_w (device, [wall][ez][ex][qz][qx]); recomputes psi."""
+        self._check_f64(tau_dev, self.n_tau, "tau")
         _lib.check(_lib.lib().dg_update_wall_shear(self.handle, _dptr(tau_dev), _stream_ptr(stream)))
+
+    def wall_shear_nodes(self, u, out=None, stream=None):
+        """Nodal wall shear stress of both walls from the FP64 velocity u,
+        returned as a (2, nz, nx) float64 device tensor."""
+        import torch
+        self._check_f64(u, self.n_vel, "u")
+        if out is None:
+            out = torch.empty((2, self.params.nz, self.params.nx), dtype=torch.float64, device=self.device)
+        self._check_f64(out, self.n_wall_nodes, "out")
+        _lib.check(_lib.lib().dg_wall_shear_nodes(self.handle, _dptr(u), _dptr(out), _stream_ptr(stream)))
+        return out
+
+    def update_wall_shear_nodes(self, tau_nodes, stream=None):
+        """Nodal tau_w (device, [wall][jz][jx]); recomputes psi with the
+        bilinear wall field."""
+        self._check_f64(tau_nodes, self.n_wall_nodes, "tau_nodes")
+        _lib.check(_lib.lib().dg_update_wall_shear_nodes(self.handle, _dptr(tau_nodes), _stream_ptr(stream)))
 
     def solve_params(self, rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5, inner_rtol=0.0,
                      multigrid=True, coarse_degree=3):

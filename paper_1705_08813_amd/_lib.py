@@ -57,6 +57,8 @@ _SIGS = {
     "dg_setup_mesh": (ctypes.c_int, [ctypes.POINTER(MeshParams), ctypes.POINTER(ctypes.c_double), _VP,
                                      ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     "dg_update_wall_shear": (ctypes.c_int, [_VP, _VP, _VP]),
+    "dg_wall_shear_nodes": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "dg_update_wall_shear_nodes": (ctypes.c_int, [_VP, _VP, _VP]),
     "dg_num_dofs": (ctypes.c_int64, [_VP, ctypes.c_int]),
     "dg_num_enriched": (ctypes.c_int64, [_VP]),
     "dg_destroy_mesh": (None, [_VP]),

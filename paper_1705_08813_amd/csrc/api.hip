@@ -16,7 +16,7 @@ thread_local std::string g_err;
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 struct WsLayout {
-  size_t eta, hy, tab_u, tab_p, tau, psi, diag, diag32, geo, meas, tauF, wdist;
+  size_t eta, hy, tab_u, tab_p, tau, tau_nodes, ws_part, psi, diag, diag32, geo, meas, tauF, wdist;
   size_t mg_hy[kMaxLevels], mg_diag[kMaxLevels], mg_diag32[kMaxLevels];
   size_t cinv, cinv32, cscr;  // coarsest pseudo-inverse (FP64, FP32) and its assembly scratch
   size_t total;
@@ -105,6 +105,9 @@ WsLayout layout(const dg_mesh& m) {
   L.tab_p = o;
   o = up256(o + sizeof(double) * (tab_layout(m.np_p, m.P.nq_p, m.P.nq_p).size + poi_ops(m.np_p).size));
   L.tau = o; o = up256(o + sizeof(double) * m.n_tau);
+  const size_t nwall = m.curved || m.P.fully_periodic ? 0 : 2 * (size_t)m.P.nz * m.P.nx;
+  L.tau_nodes = o; o = up256(o + sizeof(double) * nwall);
+  L.ws_part = o; o = up256(o + sizeof(double) * 12 * nwall);
   L.psi = o; o = up256(o + sizeof(double) * 4 * (size_t)m.nenr * m.psi_pts);
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
   L.diag32 = o; o = up256(o + sizeof(float) * m.n_p);
@@ -188,6 +191,8 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   m->tab_u = reinterpret_cast<double*>(base + W.tab_u);
   m->tab_p = reinterpret_cast<double*>(base + W.tab_p);
   m->tau = reinterpret_cast<double*>(base + W.tau);
+  m->tau_nodes = reinterpret_cast<double*>(base + W.tau_nodes);
+  m->ws_part = reinterpret_cast<double*>(base + W.ws_part);
   m->psi = reinterpret_cast<double*>(base + W.psi);
   m->diag = reinterpret_cast<double*>(base + W.diag);
   m->diag32 = reinterpret_cast<float*>(base + W.diag32);
@@ -293,6 +298,28 @@ int dg_update_wall_shear(dg_mesh* m, const double* tau_w_dev, void* stream) {
   int rc = check_hip(hipMemcpyAsync(m->tau, tau_w_dev, sizeof(double) * m->n_tau, hipMemcpyDeviceToDevice, s),
                      "tau copy");
   if (rc) return rc;
+  m->tau_nodal = 0;
+  return launch_psi(m, s);
+}
+
+int dg_wall_shear_nodes(const dg_mesh* m, const double* u, double* tau_nodes, void* stream) {
+  if (!m || !u || !tau_nodes) return set_error(DG_ERR_ARG, "mesh/u/tau_nodes is NULL");
+  if (m->curved || m->P.fully_periodic)
+    return set_error(DG_ERR_UNSUPPORTED, "nodal wall shear stress: flat no-slip walls only");
+  if (!aligned256(u) || !aligned256(tau_nodes)) return set_error(DG_ERR_ARG, "u and tau_nodes must be 256-byte aligned");
+  return launch_wall_shear_nodes(m, u, tau_nodes, static_cast<hipStream_t>(stream));
+}
+
+int dg_update_wall_shear_nodes(dg_mesh* m, const double* tau_nodes, void* stream) {
+  if (!m || !tau_nodes) return set_error(DG_ERR_ARG, "mesh/tau_nodes is NULL");
+  if (m->curved || m->P.fully_periodic)
+    return set_error(DG_ERR_UNSUPPORTED, "nodal wall shear stress: flat no-slip walls only");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n = 2 * (size_t)m->P.nz * m->P.nx;
+  int rc = check_hip(hipMemcpyAsync(m->tau_nodes, tau_nodes, sizeof(double) * n, hipMemcpyDeviceToDevice, s),
+                     "tau_nodes copy");
+  if (rc) return rc;
+  m->tau_nodal = 1;
   return launch_psi(m, s);
 }
 

@@ -144,7 +144,10 @@ struct dg_mesh {
   double* eta;            // ny+1 wall-normal vertex coordinates
   double* tab_u;          // velocity tables (np_u, nq_u, nq_wn)
   double* tab_p;          // pressure tables (np_p, nq_p, nq_p)
-  double* tau;            // wall shear stress copy
+  double* tau;            // wall shear stress copy, per wall-face Gauss point
+  double* tau_nodes;      // nodal wall shear stress copy [wall][nz][nx] (flat walls)
+  int tau_nodal = 0;      // 1: psi was computed from tau_nodes, 0: from tau
+  double* ws_part;        // wall shear scratch: [wall][ez][ex][corner][c] (flat walls)
   double* psi;            // [enr][psi_pts][4]: psi, dpsi/dx, dpsi/dy, dpsi/dz
   double* diag;           // Poisson diagonal (FP64)
   float* diag32;          // Poisson diagonal (FP32 copy)
@@ -207,6 +210,8 @@ size_t solve_bytes_mesh(const dg_mesh& m);
 // device data of the hierarchy (levels' heights and diagonals, coarse inverse)
 int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+// nodal wall shear stress [wall][nz][nx] of the FP64 velocity u (flat walls)
+int launch_wall_shear_nodes(const dg_mesh* m, const double* u, double* out, hipStream_t s);
 int64_t batch_workspace_bytes(int n);
 
 int launch_velocity_batched(const dg_mesh* const* meshes, int n, dg_prec prec, const void* const* u, void* const* r,

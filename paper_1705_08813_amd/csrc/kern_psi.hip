@@ -8,10 +8,15 @@
 //   grad psi = U'(y+) sqrt(tau_w)/nu grad y_h
 //
 // y_h is the wall distance (flat walls: exact, since the linear interpolation
-// of the vertex distances is exact there).  tau_w is the value of the
-// wall-face Gauss column nearest to the point (piecewise constant over the
-// cell's wall footprint, zero gradient).  The tables are computed once per
-// wall-shear update and stored, as the paper does for its enrichment.
+// of the vertex distances is exact there).  tau_w comes from one of two
+// fields:
+//  - per point: the value of the wall-face Gauss column nearest to the point
+//    (piecewise constant over the cell's wall footprint, zero gradient);
+//  - nodal (flat walls): tau_w,h = sum_B N_B tau_w,B with the bilinear hats of
+//    the wall vertices, constant along the wall normal, and the chain rule
+//    grad y+ = sqrt(tau_w)/nu grad y_h + y_h/(2 nu sqrt(tau_w)) grad tau_w.
+// The tables are computed once per wall-shear update and stored, as the
+// paper does for its enrichment.
 #include "kern_common.h"
 
 namespace dgwm {
@@ -77,7 +82,8 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
                            const double* __restrict__ pts, const double* __restrict__ tau, double nu, double kappa,
                            double B, int64_t nenr, int psi_pts, double* __restrict__ psi,
                            const double* __restrict__ geo, int geo_stride, const double* __restrict__ wdist,
-                           int psi_kind, double A_plus, const VdTable vd) {
+                           int psi_kind, double A_plus, const VdTable vd, const double* __restrict__ tau_nodes,
+                           double hx, double hz) {
   constexpr int NPTS = NQ * NQY * NQ;
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gid >= nenr * psi_pts) return;
@@ -90,14 +96,15 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
   const bool lower = (slot == lower_slot);
   const int ey = lower ? 0 : ny - 1;
   const double* gy = pts + NQ;
-  // reference coordinates (x, wall-normal) of the point and its tau column
-  double xiy, xix;
+  // reference coordinates of the point and its tau column
+  double xiy, xix, xiz;
   int qx, qz;
   if (pt < NPTS) {
     qx = pt % NQ;
     xix = pts[qx];
     xiy = gy[(pt / NQ) % NQY];
     qz = pt / (NQ * NQY);
+    xiz = pts[qz];
   } else {
     int f = 0, o = NPTS;
     while (pt >= o + psi_face_points(NQ, NQY, f / 2)) {
@@ -112,16 +119,19 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
       xix = (double)s;
       xiy = gy[q1];
       qz = q2;
+      xiz = pts[q2];
     } else if (d == 1) {
       qx = q1;
       xix = pts[q1];
       xiy = (double)s;
       qz = q2;
+      xiz = pts[q2];
     } else {
       qx = q1;
       xix = pts[q1];
       xiy = gy[q2];
       qz = s ? NQ - 1 : 0;
+      xiz = (double)s;
     }
   }
   double yh, gyh[3];
@@ -142,7 +152,19 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
     for (int dd = 0; dd < 3; ++dd) gyh[dd] = gx * Ji[0 * 3 + dd] + gyy * Ji[1 * 3 + dd];
   }
   const int w = lower ? 0 : 1;
-  const double tw = tau[(((int64_t)w * nz + ez) * nx + ex) * NQ * NQ + (int64_t)qz * NQ + qx];
+  double tw, gtx = 0.0, gtz = 0.0;
+  if (tau_nodes) {
+    // wall vertices (ex, ez) .. (ex+1, ez+1) on the periodic vertex grid
+    const double* tn = tau_nodes + (int64_t)w * nz * nx;
+    const int jx = ex + 1 == nx ? 0 : ex + 1, jz = ez + 1 == nz ? 0 : ez + 1;
+    const double t00 = tn[(int64_t)ez * nx + ex], t10 = tn[(int64_t)ez * nx + jx];
+    const double t01 = tn[(int64_t)jz * nx + ex], t11 = tn[(int64_t)jz * nx + jx];
+    tw = (1.0 - xiz) * ((1.0 - xix) * t00 + xix * t10) + xiz * ((1.0 - xix) * t01 + xix * t11);
+    gtx = ((1.0 - xiz) * (t10 - t00) + xiz * (t11 - t01)) / hx;
+    gtz = ((1.0 - xix) * (t01 - t00) + xix * (t11 - t10)) / hz;
+  } else {
+    tw = tau[(((int64_t)w * nz + ez) * nx + ex) * NQ * NQ + (int64_t)qz * NQ + qx];
+  }
   double* o = psi + gid * 4;
   if (!(tw > 0.0) || !isfinite(tw)) {
     o[0] = o[1] = o[2] = o[3] = __builtin_nan("");
@@ -154,10 +176,12 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
     vandriest_eval(fmax(yh, 0.0) * st, kappa, A_plus, vd, U, dU);
   else
     spalding_root(fmax(yh, 0.0) * st, kappa, B, U, dU);
+  // y+ depends on tau_w through sqrt(tau_w): d y+/d tau_w = y_h / (2 nu sqrt(tau_w))
+  const double dt = yh / (2.0 * nu * sqrt(tw));
   o[0] = U;
-  o[1] = dU * st * gyh[0];
+  o[1] = dU * st * gyh[0] + dU * dt * gtx;
   o[2] = dU * st * gyh[1];
-  o[3] = dU * st * gyh[2];
+  o[3] = dU * st * gyh[2] + dU * dt * gtz;
 }
 
 }  // namespace
@@ -176,7 +200,7 @@ int launch_psi(const dg_mesh* m, hipStream_t s) {
     hipLaunchKernelGGL((psi_kernel<a, b>), dim3(nb), dim3(128), 0, s, m->P.nx, m->P.ny, m->P.nz, lower_slot, \
                        m->n_enr_layers, m->eta, pts, m->tau, m->P.nu, m->P.kappa, m->P.B, m->nenr,          \
                        m->psi_pts, m->psi, m->geo, m->geo_stride, m->wdist, m->P.psi_kind, m->P.A_plus,      \
-                       m->vd);                                                                               \
+                       m->vd, m->tau_nodal ? m->tau_nodes : nullptr, m->hx, m->hz);                          \
     return check_hip(hipGetLastError(), "psi kernel launch");                                                \
   }
   DG_PSI_COMBOS(X)
