@@ -253,6 +253,33 @@ def main():
                                                                  + 4 * m.nq_u * m.nq_wn)}
         del vmesh
     if not args.no_extras:
+        # wall-shear pipeline (Sec. 3.2) on the same mesh and u: nodal tau_w from u, psi refresh
+        # from the nodal field, then the residual with that psi
+        print("bench: nodal wall shear pipeline", file=sys.stderr, flush=True)
+        tn = mesh.wall_shear_nodes(u)
+        for _ in range(3):
+            mesh.wall_shear_nodes(u, tn)
+            mesh.update_wall_shear_nodes(tn)
+        ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        nrep = max(10, K)
+        ev3[0].record(stream)
+        for _ in range(nrep):
+            mesh.wall_shear_nodes(u, tn)
+        ev3[1].record(stream)
+        for _ in range(nrep):
+            mesh.update_wall_shear_nodes(tn)
+        ev3[2].record(stream)
+        torch.cuda.synchronize()
+        nwall = 2 * m.nx * m.nz
+        # algorithmic bytes: u of the wall cells, their enrichment dofs, dpsi/dy at the wall-face points, tau out
+        ws_bytes = 8 * nwall * (3 * (m.k_u + 1) ** 3 + 3 + m.nq_u ** 2 + 1)
+        t_ws = ev3[0].elapsed_time(ev3[1]) / nrep
+        extras["wall_shear"] = {"wall_nodes": nwall, "wall_shear_nodes_ms": t_ws,
+                                "alg_bytes": ws_bytes, "GBps_alg": ws_bytes / (t_ws * 1e-3) / 1e9,
+                                "nodal_psi_refresh_ms": ev3[1].elapsed_time(ev3[2]) / nrep}
+        mesh.update_wall_shear(tau)   # back to the per-point field of the timed steps
+        del tn
+    if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)
         wc = PRESETS["curved"]
