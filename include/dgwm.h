@@ -82,6 +82,8 @@ typedef struct {
   double theta;           /* adjoint-term sign of the viscous form (+1 symmetric IP)      */
   int32_t psi_kind;       /* enrichment function: DG_PSI_SPALDING or DG_PSI_VANDRIEST     */
   double A_plus;          /* van Driest damping constant A+ (paper: 26)                   */
+  double yplus_off;       /* > 0: switch-off threshold of the enrichment (paper: 30), see   */
+                          /*      dg_update_wall_shear; 0: the enrichment is always on      */
 } dg_mesh_params;
 
 /* Wall laws for psi = U(y+) (paper Sec. 3.2): Spalding's implicit law with

@@ -35,7 +35,7 @@ class OrcParams(ctypes.Structure):
         ("nu", ctypes.c_double), ("kappa", ctypes.c_double), ("B", ctypes.c_double),
         ("ip_factor_u", ctypes.c_double), ("ip_factor_p", ctypes.c_double),
         ("wall_ip_mult", ctypes.c_double), ("theta", ctypes.c_double),
-        ("psi_kind", ctypes.c_int32), ("A_plus", ctypes.c_double),
+        ("psi_kind", ctypes.c_int32), ("A_plus", ctypes.c_double), ("yplus_off", ctypes.c_double),
     ]
 
 
@@ -69,6 +69,8 @@ def lib():
         L.orc_velocity_residual_nodal.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
         L.orc_psi_point_nodal.argtypes = [P, _D, ctypes.c_int64, _D, _D]
         L.orc_wall_shear_nodes.argtypes = [P, _D, _D, _D, _D]
+        L.orc_psi_volume.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D]
+        L.orc_enrichment_active.argtypes = [P, _D, _D, ctypes.POINTER(ctypes.c_int32)]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
@@ -231,6 +233,51 @@ def wall_shear_nodes(cfg, u, tau=None, tau_nodes=None):
     if rc:
         raise RuntimeError(f"orc_wall_shear_nodes failed: {rc}")
     return out.reshape(2, p.nz, p.nx)
+
+
+def enriched_cells(cfg):
+    """Cell indices of the enriched cells, in enrichment order."""
+    p = params(cfg)
+    out = []
+    # enrichment index k = ex + nx (slot + nslots ez): walk k in order
+    slots = [] if p.fully_periodic else [ey for ey in range(p.ny) if (ey == 0 and p.enrich_lower)
+                                          or (ey == p.ny - 1 and p.enrich_upper)]
+    for ez in range(p.nz):
+        for ey in slots:
+            for ex in range(p.nx):
+                out.append(ex + p.nx * (ey + p.ny * ez))
+    return np.array(out, dtype=np.int64)
+
+
+def psi_volume(cfg, cells, tau=None, tau_nodes=None):
+    """psi at the enriched volume rule points (x fastest, then the wall-normal
+    rule, then z) of the listed enriched cells: [len(cells)][nq_u nq_wn nq_u]."""
+    p = params(cfg)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    out = np.zeros((cells.size, p.nq_u * p.nq_wn * p.nq_u))
+    rc = lib().orc_psi_volume(ctypes.byref(p), _ptr(t) if t is not None else None,
+                              _ptr(tn) if tn is not None else None, cells.ctypes.data_as(_I64), cells.size,
+                              _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_psi_volume failed: {rc}")
+    return out
+
+
+def enrichment_active(cfg, tau=None, tau_nodes=None):
+    """Switch-off rule (Sec. 3.2): 1 where the enrichment of an enriched cell
+    is on, in enrichment order."""
+    p = params(cfg)
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    out = np.zeros(num_enriched(cfg), dtype=np.int32)
+    rc = lib().orc_enrichment_active(ctypes.byref(p), _ptr(t) if t is not None else None,
+                                     _ptr(tn) if tn is not None else None,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc:
+        raise RuntimeError(f"orc_enrichment_active failed: {rc}")
+    return out
 
 
 def poisson_apply(cfg, x, cells=None, absmode=False):

@@ -56,6 +56,8 @@ typedef struct {
   double ip_factor_u, ip_factor_p, wall_ip_mult, theta;
   int32_t psi_kind; /* 0: Spalding's law, 1: van Driest's law (Sec. 3.2, eq. psi) */
   double A_plus;    /* van Driest damping constant A+ */
+  double yplus_off; /* > 0: the enrichment of a wall cell is off while every quadrature point of
+                       the cell has y+ below this value (Sec. 3.2: 30); 0: always on */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -227,6 +229,7 @@ typedef struct {
   double qp[ORC_MAXN], wp[ORC_MAXN];
   const double *tau;  /* wall shear stress per wall-face quadrature point */
   const double *tau_nodes; /* or: nodal wall shear stress [wall][nz][nx] (Sec. 3.2, m = 1) */
+  signed char *act;   /* per enriched cell: 1 enrichment on, 0 off; NULL: all on */
 } ctx;
 
 /* Wall-normal vertex coordinate, Sec. 5.1: f(t) = tanh(gamma(2t-1))/tanh(gamma). */
@@ -386,13 +389,16 @@ static double vertex_wall_distance(const ctx *C, int ix, int iy, int w) {
 
 typedef struct { double psi, g[3]; } psi_pt;
 
-/* psi and grad(psi) at reference point xi of enriched cell e.
+/* Wall distance and wall shear stress at reference point xi of enriched cell
+ * e (Sec. 3.2), with their physical gradients (J^{-T} applied).
  * y_h: trilinear (m = 1) interpolation of the vertex wall distances.
- * tau_w: value of the wall-face Gauss column nearest to (xi_x, xi_z) in the
- * cell's velocity rule; treated as locally constant (zero gradient).
- * y+ = y_h sqrt(tau_w)/nu (rho = 1), psi = U(y+) of the chosen law,
- * grad psi = U'(y+) sqrt(tau_w)/nu grad y_h. */
-static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double Ji[3][3], psi_pt *out) {
+ * tau_w: either the value of the wall-face Gauss column nearest to
+ * (xi_x, xi_z) in the cell's velocity rule, treated as locally constant
+ * (zero gradient), or, with nodal values, the bilinear interpolation
+ * tau_w,h = sum_B N_B tau_w,B of the wall vertices, constant along the wall
+ * normal (flat walls: x and z are affine in xi_x and xi_z). */
+static void wall_fields(const ctx *C, int64_t e, const double xi[3], const double Ji[3][3], double *yh_out,
+                        double gyh[3], double *tw_out, double gtw[3]) {
   int ex, ey, ez;
   cell_index(C, e, &ex, &ey, &ez);
   int w = (ey == 0) ? 0 : 1;
@@ -412,15 +418,11 @@ static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double J
         gr[1] += dv[c][b][a] * lx * sy * lz;
         gr[2] += dv[c][b][a] * lx * ly * sz;
       }
-  double gyh[3];
   for (int d = 0; d < 3; ++d) gyh[d] = gr[0] * Ji[0][d] + gr[1] * Ji[1][d] + gr[2] * Ji[2][d];
-  double tw, gtw[3] = {0, 0, 0};
+  double tw = 0;
+  gtw[0] = gtw[1] = gtw[2] = 0;
   if (C->tau_nodes) {
-    /* Sec. 3.2: tau_w,h = sum_B N_B tau_w,B with the bilinear (m = 1) hat
-     * functions of the wall vertices, extended constant along the wall
-     * normal; x and z are affine in the reference coordinates */
     double hx = C->P.Lx / C->P.nx, hz = C->P.Lz / C->P.nz;
-    tw = 0;
     for (int c = 0; c < 2; ++c)
       for (int a = 0; a < 2; ++a) {
         int jx = (ex + a) % C->P.nx, jz = (ez + c) % C->P.nz;
@@ -440,6 +442,23 @@ static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double J
     int64_t ti = (((int64_t)w * C->P.nz + ez) * C->P.nx + ex) * nq * nq + (int64_t)qz * nq + qx;
     tw = C->tau[ti];
   }
+  *yh_out = yh;
+  *tw_out = tw;
+}
+
+/* psi and grad(psi) at reference point xi of enriched cell e:
+ * y+ = y_h sqrt(tau_w)/nu (rho = 1), psi = U(y+) of the chosen law and
+ * grad psi = U'(y+) grad y+ with
+ * grad y+ = sqrt(tau_w)/nu grad y_h + y_h / (2 nu sqrt(tau_w)) grad tau_w.
+ * A cell whose enrichment is switched off has psi = 0. */
+static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double Ji[3][3], psi_pt *out) {
+  if (C->act && !C->act[C->enr[e]]) {
+    out->psi = 0;
+    out->g[0] = out->g[1] = out->g[2] = 0;
+    return;
+  }
+  double yh, gyh[3], tw, gtw[3];
+  wall_fields(C, e, xi, Ji, &yh, gyh, &tw, gtw);
   double st = sqrt(tw) / C->P.nu;
   double U, dU;
   if (C->P.psi_kind == 1)
@@ -447,8 +466,34 @@ static void eval_psi(const ctx *C, int64_t e, const double xi[3], const double J
   else
     orc_spalding(yh * st, C->P.kappa, C->P.B, &U, &dU);
   out->psi = U;
-  /* grad y+ = sqrt(tau)/nu grad y_h + y_h / (2 nu sqrt(tau)) grad tau */
   for (int d = 0; d < 3; ++d) out->g[d] = dU * (st * gyh[d] + yh / (2.0 * C->P.nu * sqrt(tw)) * gtw[d]);
+}
+
+/* Switch-off rule of Sec. 3.2: the enrichment of a wall cell is on when at
+ * least one quadrature point of the cell (its enriched volume rule) has
+ * y+ >= yplus_off.  Sets C->act (all on when yplus_off <= 0). */
+static int cell_on(const ctx *C, int64_t e) {
+  const double *q[3], *w[3];
+  int nq[3];
+  for (int a = 0; a < 3; ++a) { q[a] = vel_q(C, e, a, &w[a]); nq[a] = vel_nq(C, e, a); }
+  for (int c = 0; c < nq[2]; ++c)
+    for (int b = 0; b < nq[1]; ++b)
+      for (int a = 0; a < nq[0]; ++a) {
+        double xi[3] = {q[0][a], q[1][b], q[2][c]}, X[3], J[3][3], Ji[3][3], yh, gyh[3], tw, gtw[3];
+        cell_map(C, e, xi, X, J);
+        inv3(J, Ji);
+        wall_fields(C, e, xi, Ji, &yh, gyh, &tw, gtw);
+        if (yh * sqrt(tw) / C->P.nu >= C->P.yplus_off) return 1;
+      }
+  return 0;
+}
+
+/* Activity of every enriched cell (only `one` when one >= 0). */
+static void ctx_activity(ctx *C, int64_t one) {
+  if (!(C->P.yplus_off > 0) || C->nenr == 0) return;
+  C->act = (signed char *)malloc((size_t)C->nenr);
+  for (int64_t e = 0; e < C->ncell; ++e)
+    if (C->enr[e] >= 0 && (one < 0 || e == one)) C->act[C->enr[e]] = (signed char)cell_on(C, e);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -549,6 +594,7 @@ static int ctx_init(ctx *C, const orc_params *P, const double *tau) {
 static void ctx_free(ctx *C) {
   free(C->eta);
   free(C->enr);
+  free(C->act);
 }
 
 int64_t orc_num_dofs(const orc_params *P, int field) {
@@ -736,6 +782,7 @@ static int velocity_residual(const orc_params *P, const double *u, const double 
   if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  ctx_activity(&C, -1);
   int n = C.npu, np3 = n * n * n;
   int err = 0;
 #pragma omp parallel
@@ -918,6 +965,7 @@ int orc_psi_point(const orc_params *P, const double *tau_w, int64_t e, const dou
   ctx C;
   if (ctx_init(&C, P, tau_w)) return -1;
   if (e < 0 || e >= C.ncell || C.enr[e] < 0) { ctx_free(&C); return -2; }
+  ctx_activity(&C, e);
   double X[3], J[3][3], Ji[3][3];
   cell_map(&C, e, xi, X, J);
   inv3(J, Ji);
@@ -937,6 +985,7 @@ int orc_psi_point_nodal(const orc_params *P, const double *tau_nodes, int64_t e,
   if (ctx_init(&C, P, NULL)) return -1;
   C.tau_nodes = tau_nodes;
   if (e < 0 || e >= C.ncell || C.enr[e] < 0) { ctx_free(&C); return -2; }
+  ctx_activity(&C, e);
   double X[3], J[3][3], Ji[3][3];
   cell_map(&C, e, xi, X, J);
   inv3(J, Ji);
@@ -944,6 +993,52 @@ int orc_psi_point_nodal(const orc_params *P, const double *tau_nodes, int64_t e,
   eval_psi(&C, e, xi, Ji, &pt);
   out4[0] = pt.psi;
   out4[1] = pt.g[0]; out4[2] = pt.g[1]; out4[3] = pt.g[2];
+  ctx_free(&C);
+  return 0;
+}
+
+/* psi at the points of the enriched volume rule (nq_u x nq_wn x nq_u, x
+ * fastest) of each listed enriched cell, from the per-point tau_w or, when
+ * given, the nodal tau_nodes; out: [ncells][points]. */
+int orc_psi_volume(const orc_params *P, const double *tau_w, const double *tau_nodes, const int64_t *cells,
+                   int64_t ncells, double *out) {
+  ctx C;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  int err = 0;
+  for (int64_t i = 0; i < ncells; ++i)
+    if (cells[i] < 0 || cells[i] >= C.ncell || C.enr[cells[i]] < 0) err = -3;
+  if (err) { ctx_free(&C); return err; }
+  ctx_activity(&C, -1);
+  int nq = P->nq_u, nw = P->nq_wn, npts = nq * nw * nq;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < ncells; ++i) {
+    int64_t e = cells[i];
+    for (int c = 0; c < nq; ++c)
+      for (int b = 0; b < nw; ++b)
+        for (int a = 0; a < nq; ++a) {
+          double xi[3] = {C.qu[a], C.qwn[b], C.qu[c]}, X[3], J[3][3], Ji[3][3];
+          cell_map(&C, e, xi, X, J);
+          inv3(J, Ji);
+          psi_pt pt;
+          eval_psi(&C, e, xi, Ji, &pt);
+          out[i * npts + a + nq * (b + nw * c)] = pt.psi;
+        }
+  }
+  ctx_free(&C);
+  return 0;
+}
+
+/* Enrichment on (1) or off (0) per enriched cell under the switch-off rule
+ * of Sec. 3.2 (all 1 when yplus_off <= 0); out: nenr flags. */
+int orc_enrichment_active(const orc_params *P, const double *tau_w, const double *tau_nodes, int32_t *out) {
+  ctx C;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  ctx_activity(&C, -1);
+  for (int64_t k = 0; k < C.nenr; ++k) out[k] = C.act ? C.act[k] : 1;
   ctx_free(&C);
   return 0;
 }
@@ -963,6 +1058,7 @@ int orc_wall_shear_nodes(const orc_params *P, const double *u, const double *tau
   if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  ctx_activity(&C, -1);
   int nx = P->nx, nz = P->nz, nq = P->nq_u, n = C.npu, np3 = n * n * n;
   double hx = P->Lx / nx, hz = P->Lz / nz;
   double *num = (double *)calloc((size_t)2 * nz * nx * 3, sizeof(double));

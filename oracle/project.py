@@ -1,0 +1,94 @@
+"""Cell-wise L2 projection onto the refreshed enriched space (arXiv
+1705.08813, Sec. 3.2, eq. l2).
+
+TEST INFRASTRUCTURE ONLY (never used by the product).
+
+When the wall shear stress changes, the enrichment function of every
+enriched cell changes from psi_old to psi_new, and the velocity is carried
+into the new space cell by cell:
+
+    int_e v . u_new dOmega = int_e v . u_old dOmega   for every v of the new local space.
+
+The new local space of an enriched cell is span{N_B e_c} together with
+psi_new e_c while its enrichment is on, the polynomial span alone while it is
+switched off (psi_new identically zero); u_old = u_bar_old + psi_old u~_old.
+With the enriched cell's quadrature rule (nq_u x nq_wn x nq_u Gauss points,
+weights w_q times |det J|) eq. l2 is the normal equation of the weighted
+least-squares problem  min_x || W^{1/2} (Phi x - u_old) ||  with Phi the new
+local basis evaluated at the points: every enriched cell forms Phi directly
+from 3-D basis values and solves that problem with numpy's least-squares
+routine (SVD), which gives the solution of eq. l2 without squaring the
+condition number of the mass matrix Phi^T W Phi (about 5e6 when psi is close
+to a polynomial on the cell).  The three velocity components decouple (the
+basis is componentwise).  Cells without enrichment
+keep their values, since their space does not change.
+
+psi_old and psi_new are given as values at those quadrature points
+([enriched cell][point], x fastest, then the wall-normal rule, then z), so
+that tests can also feed synthetic fields.  Flat (box) meshes only.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import enriched_cells, gauss, gauss_lobatto, lagrange, vertex_eta
+
+
+def volume_rule(cfg):
+    """Reference points (npts, 3) and weights of the enriched volume rule."""
+    qu, wu = gauss(cfg.nq_u)
+    qw, ww = gauss(cfg.nq_wn)
+    pts, wts = [], []
+    for c in range(cfg.nq_u):
+        for b in range(cfg.nq_wn):
+            for a in range(cfg.nq_u):
+                pts.append((qu[a], qw[b], qu[c]))
+                wts.append(wu[a] * ww[b] * wu[c])
+    return np.array(pts), np.array(wts)
+
+
+def basis_at(cfg, pts):
+    """N_B at the points, B = i + n (j + n m): array (npts, n^3)."""
+    n = cfg.k_u + 1
+    nodes = gauss_lobatto(n)
+    V = np.zeros((len(pts), n ** 3))
+    for q, (x, y, z) in enumerate(pts):
+        vx, vy, vz = lagrange(nodes, x)[0], lagrange(nodes, y)[0], lagrange(nodes, z)[0]
+        V[q] = np.einsum("m,j,i->mji", vz, vy, vx).reshape(-1)
+    return V
+
+
+def project(cfg, u_old, psi_old, psi_new, return_cond=False):
+    """u_new of eq. l2.  psi_old, psi_new: [nenr][npts] values at the enriched
+    volume rule.  With return_cond, also the 2-norm condition number of each
+    enriched cell's mass matrix."""
+    if cfg.wall_amp != 0.0:
+        raise ValueError("flat meshes only")
+    n3 = (cfg.k_u + 1) ** 3
+    u_old = np.asarray(u_old, dtype=np.float64)
+    u_new = u_old.copy()
+    cells = enriched_cells(cfg)
+    pts, wts = volume_rule(cfg)
+    V = basis_at(cfg, pts)
+    eta = vertex_eta(cfg)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    off = cfg.ncell * 3 * n3
+    conds = np.zeros(len(cells))
+    for k, e in enumerate(cells):
+        ey = (e // cfg.nx) % cfg.ny
+        detJ = hx * (eta[ey + 1] - eta[ey]) * hz
+        w = wts * detJ
+        po, pn = np.asarray(psi_old[k], dtype=float), np.asarray(psi_new[k], dtype=float)
+        on = bool(np.any(pn != 0.0))
+        Phi = np.hstack([V, pn[:, None]]) if on else V           # new local basis at the points
+        sw = np.sqrt(w)
+        A = sw[:, None] * Phi
+        conds[k] = np.linalg.cond(A.T @ A)
+        for c in range(3):
+            ub = u_old[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
+            ut = u_old[off + 3 * k + c]
+            uq = V @ ub + po * ut                                # u_old at the points
+            x = np.linalg.lstsq(A, sw * uq, rcond=None)[0]
+            u_new[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = x[:n3]
+            u_new[off + 3 * k + c] = x[n3] if on else 0.0
+    return (u_new, conds) if return_cond else u_new

@@ -55,6 +55,8 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
     return set_error(DG_ERR_ARG, "psi_kind must be DG_PSI_SPALDING or DG_PSI_VANDRIEST");
   if (P.psi_kind == DG_PSI_VANDRIEST && !(P.A_plus > 0 && std::isfinite(P.A_plus)))
     return set_error(DG_ERR_ARG, "A_plus must be positive and finite");
+  if (!(P.yplus_off >= 0) || !std::isfinite(P.yplus_off))
+    return set_error(DG_ERR_ARG, "yplus_off must be >= 0 and finite");
   if (P.wall_amp != 0.0 && P.fully_periodic) return set_error(DG_ERR_ARG, "a curved wall needs walls");
   if (!(std::fabs(P.wall_amp) < 0.9)) return set_error(DG_ERR_ARG, "wall amplitude must be below 0.9");
   m.P = P;

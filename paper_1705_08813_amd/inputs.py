@@ -50,6 +50,7 @@ class MeshConfig:
     theta: float = 1.0
     psi_kind: int = 0          # 0: Spalding's law, 1: van Driest's law
     A_plus: float = 26.0
+    yplus_off: float = 0.0     # > 0: switch a wall cell's enrichment off while all its points have y+ below this
 
     def as_dict(self):
         return asdict(self)

@@ -39,7 +39,8 @@ def test_workspace_sizes_and_argument_errors():
         assert ws_bytes(PRESETS[name].mesh) > 0
     good = PRESETS["tiny"].mesh
     bad = [good.with_(nx=0), good.with_(ny=1), good.with_(k_u=0), good.with_(nu=-1.0), good.with_(nq_u=40),
-           good.with_(ip_factor_u=0.0), good.with_(gamma=float("nan"))]
+           good.with_(ip_factor_u=0.0), good.with_(gamma=float("nan")), good.with_(yplus_off=-1.0),
+           good.with_(yplus_off=float("inf"))]
     for cfg in bad:
         assert ws_bytes(cfg) == -1, cfg
     assert ws_bytes(good.with_(k_u=6, nq_u=3)) == -6  # combination not compiled
