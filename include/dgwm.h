@@ -115,7 +115,13 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
 
 /* Replace tau_w (device array, tau_w layout, FP64) and recompute psi and grad
  * psi in FP64 (paper Sec. 3.2: the wall shear stress and with it the
- * enrichment space are updated once per time step).  Enqueued on `stream`. */
+ * enrichment space are updated once per time step).  Enqueued on `stream`.
+ * Switch-off (paper Sec. 3.2): with yplus_off > 0, the enrichment of an
+ * enriched cell is off while every point of its volume rule (nq_u x nq_wn x
+ * nq_u) has y+ = y_h sqrt(tau_w)/nu below yplus_off; such a cell gets psi = 0
+ * and grad psi = 0, so its enrichment unknowns decouple (their residual rows
+ * are zero).  The psi table and activity flags in force before the update
+ * are kept as the previous space for dg_project_velocity. */
 int dg_update_wall_shear(dg_mesh* mesh, const double* tau_w_dev, void* stream);
 
 /* Nodal wall shear stress of both walls from the FP64 velocity u (paper
@@ -146,6 +152,26 @@ int dg_wall_shear_nodes(const dg_mesh* mesh, const double* u, double* tau_nodes,
  * Flat no-slip walls only (DG_ERR_UNSUPPORTED otherwise).  Enqueued on
  * `stream`. */
 int dg_update_wall_shear_nodes(dg_mesh* mesh, const double* tau_nodes, void* stream);
+
+/* Cell-wise L2 projection of a velocity from the space before the last
+ * wall-shear update onto the current one (paper Sec. 3.2, eq. l2):
+ *   (v, u_new)_e = (v, u_old)_e  for every v of the current local space,
+ * per component and enriched cell, with the enriched cell's quadrature rule;
+ * the local space is span{N_B} plus psi_new while the cell's enrichment is
+ * on, the polynomials alone while it is off.  Cells without enrichment are
+ * copied.  Before any update (or right after setup) this is the identity up
+ * to rounding.  Call it once per vector that must follow the new space, after
+ * dg_update_wall_shear(_nodes) and before the next update.
+ *   u_old, u_new: device, dg_num_dofs(mesh, 0) doubles each.  u_new may be
+ *                 u_old: the projection then runs in place and rewrites only
+ *                 the enriched cells' entries.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall), DG_ERR_HIP. */
+int dg_project_velocity(const dg_mesh* mesh, const double* u_old, double* u_new, void* stream);
+
+/* Copy the enrichment activity flags (1 on, 0 switched off; see
+ * dg_update_wall_shear) of the current space to the device array flags
+ * (dg_num_enriched(mesh) int32 values, in enriched-cell order). */
+int dg_enrichment_active(const dg_mesh* mesh, int32_t* flags, void* stream);
 
 /* Number of entries of the velocity (field 0, polynomial + enrichment) or
  * pressure (field 1) vector; negative on error. */

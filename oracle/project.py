@@ -58,10 +58,11 @@ def basis_at(cfg, pts):
     return V
 
 
-def project(cfg, u_old, psi_old, psi_new, return_cond=False):
+def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
     """u_new of eq. l2.  psi_old, psi_new: [nenr][npts] values at the enriched
     volume rule.  With return_cond, also the 2-norm condition number of each
-    enriched cell's mass matrix."""
+    enriched cell's mass matrix.  only: enriched-cell positions to project
+    (the projection is cell-local; the others keep u_old)."""
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -74,7 +75,9 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False):
     hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
     off = cfg.ncell * 3 * n3
     conds = np.zeros(len(cells))
-    for k, e in enumerate(cells):
+    todo = range(len(cells)) if only is None else sorted(set(int(k) for k in only))
+    for k in todo:
+        e = cells[k]
         ey = (e // cfg.nx) % cfg.ny
         detJ = hx * (eta[ey + 1] - eta[ey]) * hz
         w = wts * detJ

@@ -134,6 +134,26 @@ class Mesh:
         self._check_f64(tau_nodes, self.n_wall_nodes, "tau_nodes")
         _lib.check(_lib.lib().dg_update_wall_shear_nodes(self.handle, _dptr(tau_nodes), _stream_ptr(stream)))
 
+    def project_velocity(self, u_old, u_new=None, stream=None):
+        """L2 projection (eq. l2) of u_old from the space before the last
+        wall-shear update onto the current one; returns u_new (u_new may be
+        u_old: in place)."""
+        import torch
+        self._check_f64(u_old, self.n_vel, "u_old")
+        if u_new is None:
+            u_new = torch.empty_like(u_old)
+        self._check_f64(u_new, self.n_vel, "u_new")
+        _lib.check(_lib.lib().dg_project_velocity(self.handle, _dptr(u_old), _dptr(u_new), _stream_ptr(stream)))
+        return u_new
+
+    def enrichment_active(self, stream=None):
+        """Activity flags (int32 device tensor, 1 on / 0 switched off) of the
+        enriched cells in the current space."""
+        import torch
+        out = torch.empty(max(self.n_enriched, 1), dtype=torch.int32, device=self.device)
+        _lib.check(_lib.lib().dg_enrichment_active(self.handle, _dptr(out), _stream_ptr(stream)))
+        return out[:self.n_enriched]
+
     def solve_params(self, rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5, inner_rtol=0.0,
                      multigrid=True, coarse_degree=3):
         return SolveParams(rtol=rtol, max_outer=max_outer, max_inner=max_inner, cheb_degree=cheb_degree,

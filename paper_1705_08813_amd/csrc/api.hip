@@ -16,13 +16,53 @@ thread_local std::string g_err;
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 struct WsLayout {
-  size_t eta, hy, tab_u, tab_p, tau, tau_nodes, ws_part, psi, diag, diag32, geo, meas, tauF, wdist;
+  size_t eta, hy, tab_u, tab_p, tau, tau_nodes, ws_part, psi, psi_prev, act, act_prev, minv, diag, diag32, geo, meas,
+      tauF, wdist;
   size_t mg_hy[kMaxLevels], mg_diag[kMaxLevels], mg_diag32[kMaxLevels];
   size_t cinv, cinv32, cscr;  // coarsest pseudo-inverse (FP64, FP32) and its assembly scratch
   size_t total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Inverse of the 1-D mass matrix M_ij = sum_q w_q N_i(g_q) N_j(g_q) of a
+// Gauss rule with nq >= np points (symmetric positive definite), by
+// Gauss-Jordan elimination with partial pivoting; S is [nq][np], out [np][np].
+void inverse_mass_1d(int np, int nq, const double* S, const double* w, double* out) {
+  std::vector<double> a(np * 2 * np, 0.0);
+  for (int i = 0; i < np; ++i) {
+    for (int j = 0; j < np; ++j) {
+      double m = 0.0;
+      for (int q = 0; q < nq; ++q) m += w[q] * S[q * np + i] * S[q * np + j];
+      a[i * 2 * np + j] = m;
+    }
+    a[i * 2 * np + np + i] = 1.0;
+  }
+  for (int c = 0; c < np; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < np; ++r)
+      if (std::fabs(a[r * 2 * np + c]) > std::fabs(a[piv * 2 * np + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < 2 * np; ++k) std::swap(a[c * 2 * np + k], a[piv * 2 * np + k]);
+    const double d = 1.0 / a[c * 2 * np + c];
+    for (int k = 0; k < 2 * np; ++k) a[c * 2 * np + k] *= d;
+    for (int r = 0; r < np; ++r) {
+      if (r == c) continue;
+      const double f = a[r * 2 * np + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < 2 * np; ++k) a[r * 2 * np + k] -= f * a[c * 2 * np + k];
+    }
+  }
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) out[i * np + j] = a[i * 2 * np + np + j];
+}
+
+// The current psi table and activity flags become the previous ones; the
+// next psi launch overwrites the (old) previous buffers.
+void keep_previous_space(dg_mesh* m) {
+  std::swap(m->psi, m->psi_prev);
+  std::swap(m->act, m->act_prev);
+}
 
 }  // namespace
 
@@ -111,6 +151,10 @@ WsLayout layout(const dg_mesh& m) {
   L.tau_nodes = o; o = up256(o + sizeof(double) * nwall);
   L.ws_part = o; o = up256(o + sizeof(double) * 12 * nwall);
   L.psi = o; o = up256(o + sizeof(double) * 4 * (size_t)m.nenr * m.psi_pts);
+  L.psi_prev = o; o = up256(o + sizeof(double) * 4 * (size_t)m.nenr * m.psi_pts);
+  L.act = o; o = up256(o + sizeof(int32_t) * (size_t)m.nenr);
+  L.act_prev = o; o = up256(o + sizeof(int32_t) * (size_t)m.nenr);
+  L.minv = o; o = up256(o + sizeof(double) * 2 * m.np_u * m.np_u);
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
   L.diag32 = o; o = up256(o + sizeof(float) * m.n_p);
   L.geo = o; o = up256(o + sizeof(double) * 10 * (size_t)m.ncell * m.geo_stride);
@@ -196,6 +240,10 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   m->tau_nodes = reinterpret_cast<double*>(base + W.tau_nodes);
   m->ws_part = reinterpret_cast<double*>(base + W.ws_part);
   m->psi = reinterpret_cast<double*>(base + W.psi);
+  m->psi_prev = reinterpret_cast<double*>(base + W.psi_prev);
+  m->act = reinterpret_cast<int32_t*>(base + W.act);
+  m->act_prev = reinterpret_cast<int32_t*>(base + W.act_prev);
+  m->minv = reinterpret_cast<double*>(base + W.minv);
   m->diag = reinterpret_cast<double*>(base + W.diag);
   m->diag32 = reinterpret_cast<float*>(base + W.diag32);
   for (int l = 0; l < m->mg_nlev; ++l) {
@@ -271,7 +319,27 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
     if (!rc) rc = launch_geometry(m, s);
   }
   if (P.psi_kind == DG_PSI_VANDRIEST) vandriest_table(P.kappa, P.A_plus, m->vd);
+  // without a switch-off threshold every enriched cell stays on: both flag
+  // arrays are set once and the activity kernel never runs
+  std::vector<int32_t> ones(m->nenr > 0 && !(P.yplus_off > 0) ? m->nenr : 0, 1);
+  if (!rc && !ones.empty())
+    rc = check_hip(hipMemcpyAsync(m->act, ones.data(), sizeof(int32_t) * ones.size(), hipMemcpyHostToDevice, s),
+                   "copy");
   if (!rc) rc = launch_psi(m, s);
+  // the previous-space tables start as copies of the current ones (a
+  // projection before any update is the identity)
+  if (!rc && m->nenr > 0)
+    rc = check_hip(hipMemcpyAsync(m->psi_prev, m->psi, sizeof(double) * 4 * (size_t)m->nenr * m->psi_pts,
+                                  hipMemcpyDeviceToDevice, s), "copy");
+  if (!rc && m->nenr > 0)
+    rc = check_hip(hipMemcpyAsync(m->act_prev, m->act, sizeof(int32_t) * (size_t)m->nenr, hipMemcpyDeviceToDevice,
+                                  s), "copy");
+  std::vector<double> minv(2 * m->np_u * m->np_u);
+  inverse_mass_1d(m->np_u, P.nq_u, tu.data() + Lu.S, tu.data() + Lu.w, minv.data());
+  inverse_mass_1d(m->np_u, P.nq_wn, tu.data() + Lu.Sy, tu.data() + Lu.wy, minv.data() + m->np_u * m->np_u);
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(m->minv, minv.data(), sizeof(double) * minv.size(), hipMemcpyHostToDevice, s),
+                   "copy");
   if (!rc && !m->curved) rc = launch_poisson_diag(m, s);
   if (!rc && m->mg_nlev > 0) {
     m->mg[0].hy = m->hy;
@@ -301,6 +369,7 @@ int dg_update_wall_shear(dg_mesh* m, const double* tau_w_dev, void* stream) {
                      "tau copy");
   if (rc) return rc;
   m->tau_nodal = 0;
+  keep_previous_space(m);
   return launch_psi(m, s);
 }
 
@@ -322,7 +391,23 @@ int dg_update_wall_shear_nodes(dg_mesh* m, const double* tau_nodes, void* stream
                      "tau_nodes copy");
   if (rc) return rc;
   m->tau_nodal = 1;
+  keep_previous_space(m);
   return launch_psi(m, s);
+}
+
+int dg_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, void* stream) {
+  if (!m || !u_old || !u_new) return set_error(DG_ERR_ARG, "mesh/u_old/u_new is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "projection onto the refreshed space: flat meshes only");
+  if (!aligned256(u_old) || !aligned256(u_new)) return set_error(DG_ERR_ARG, "u_old and u_new must be 256-byte aligned");
+  return launch_project_velocity(m, u_old, u_new, static_cast<hipStream_t>(stream));
+}
+
+int dg_enrichment_active(const dg_mesh* m, int32_t* flags, void* stream) {
+  if (!m || !flags) return set_error(DG_ERR_ARG, "mesh/flags is NULL");
+  if (m->nenr == 0) return DG_OK;
+  return check_hip(hipMemcpyAsync(flags, m->act, sizeof(int32_t) * (size_t)m->nenr, hipMemcpyDeviceToDevice,
+                                  static_cast<hipStream_t>(stream)),
+                   "activity copy");
 }
 
 int64_t dg_num_dofs(const dg_mesh* m, int field) {

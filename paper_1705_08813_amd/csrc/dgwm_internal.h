@@ -149,6 +149,10 @@ struct dg_mesh {
   int tau_nodal = 0;      // 1: psi was computed from tau_nodes, 0: from tau
   double* ws_part;        // wall shear scratch: [wall][ez][ex][corner][c] (flat walls)
   double* psi;            // [enr][psi_pts][4]: psi, dpsi/dx, dpsi/dy, dpsi/dz
+  double* psi_prev;       // the same table before the last wall-shear update
+  int32_t* act;           // [enr] enrichment on (1) or switched off (0)
+  int32_t* act_prev;      // the same flags before the last wall-shear update
+  double* minv;           // inverse 1-D mass matrices [2][np_u][np_u]: x/z rule, wall-normal rule
   double* diag;           // Poisson diagonal (FP64)
   float* diag32;          // Poisson diagonal (FP32 copy)
   double* hy;             // ny cell heights, then their ny reciprocals
@@ -210,6 +214,8 @@ size_t solve_bytes_mesh(const dg_mesh& m);
 // device data of the hierarchy (levels' heights and diagonals, coarse inverse)
 int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+// u_new = L2 projection of u_old from the space of psi_prev onto that of psi
+int launch_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, hipStream_t s);
 // nodal wall shear stress [wall][nz][nx] of the FP64 velocity u (flat walls)
 int launch_wall_shear_nodes(const dg_mesh* m, const double* u, double* out, hipStream_t s);
 int64_t batch_workspace_bytes(int n);

@@ -15,6 +15,9 @@
 //  - nodal (flat walls): tau_w,h = sum_B N_B tau_w,B with the bilinear hats of
 //    the wall vertices, constant along the wall normal, and the chain rule
 //    grad y+ = sqrt(tau_w)/nu grad y_h + y_h/(2 nu sqrt(tau_w)) grad tau_w.
+// Switch-off (Sec. 3.2): the enrichment of a cell is off while every point
+// of its volume rule has y+ below yplus_off; such a cell gets psi = 0 and
+// grad psi = 0, and its flag in the activity array is 0.
 // The tables are computed once per wall-shear update and stored, as the
 // paper does for its enrichment.
 #include "kern_common.h"
@@ -71,111 +74,185 @@ __device__ void vandriest_eval(double yp, double kappa, double Ap, const VdTable
   dU = vandriest_f(yp, kappa, Ap);
 }
 
-// pts: the NQ Gauss points of the wall-parallel rule followed by the NQY
-// points of the wall-normal rule (on [0,1]).
-// Curved lower wall: y_h is the bilinear (x, eta) interpolation of the vertex
-// distances to the closest wall vertex (wdist: rows iy = 1 and iy = ny-1; the
-// wall rows are 0), grad y_h = J^{-T} grad_xi y_h with J^{-1} from the
-// geometry table at the same point.
-template <int NQ, int NQY>
-__global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, const double* __restrict__ eta,
-                           const double* __restrict__ pts, const double* __restrict__ tau, double nu, double kappa,
-                           double B, int64_t nenr, int psi_pts, double* __restrict__ psi,
-                           const double* __restrict__ geo, int geo_stride, const double* __restrict__ wdist,
-                           int psi_kind, double A_plus, const VdTable vd, const double* __restrict__ tau_nodes,
-                           double hx, double hz) {
-  constexpr int NPTS = NQ * NQY * NQ;
-  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (gid >= nenr * psi_pts) return;
-  const int64_t enr = gid / psi_pts;
-  const int pt = (int)(gid - enr * psi_pts);
-  const int ex = (int)(enr % nx);
-  const int64_t t0 = enr / nx;
-  const int slot = (int)(t0 % nslots);
-  const int ez = (int)(t0 / nslots);
-  const bool lower = (slot == lower_slot);
-  const int ey = lower ? 0 : ny - 1;
-  const double* gy = pts + NQ;
-  // reference coordinates of the point and its tau column
-  double xiy, xix, xiz;
+// Everything the point evaluations read.  pts: the NQ Gauss points of the
+// wall-parallel rule followed by the NQY points of the wall-normal rule (on
+// [0,1]).
+struct PsiArgs {
+  int nx, ny, nz, lower_slot, nslots, psi_pts, geo_stride, psi_kind;
+  int64_t nenr;
+  const double* eta;
+  const double* pts;
+  const double* tau;        // per wall-face Gauss point
+  const double* tau_nodes;  // or nodal [wall][nz][nx] (nullptr: per point)
+  const double* geo;        // curved: [cell][point][J^{-1}, weight]; nullptr: flat
+  const double* wdist;      // curved: [2][nx+1] wall-adjacent vertex distances
+  double nu, kappa, B, A_plus, hx, hz, yplus_off;
+  double* psi;
+  int32_t* act;
+  VdTable vd;
+};
+
+struct CellRef {
+  int ex, ey, ez, w;  // w: 0 lower wall, 1 upper wall
+  bool lower;
+};
+
+__device__ __forceinline__ CellRef enriched_cell(const PsiArgs& A, int64_t enr) {
+  CellRef c;
+  c.ex = (int)(enr % A.nx);
+  const int64_t t0 = enr / A.nx;
+  const int slot = (int)(t0 % A.nslots);
+  c.ez = (int)(t0 / A.nslots);
+  c.lower = (slot == A.lower_slot);
+  c.ey = c.lower ? 0 : A.ny - 1;
+  c.w = c.lower ? 0 : 1;
+  return c;
+}
+
+// Reference coordinates of point pt of the psi tables (volume rule, then the
+// six faces) and the wall-face Gauss column (qx, qz) nearest to it.
+struct PointRef {
+  double xix, xiy, xiz;
   int qx, qz;
+};
+
+template <int NQ, int NQY>
+__device__ __forceinline__ PointRef decode_point(int pt, const double* pts) {
+  constexpr int NPTS = NQ * NQY * NQ;
+  const double* gy = pts + NQ;
+  PointRef r;
   if (pt < NPTS) {
-    qx = pt % NQ;
-    xix = pts[qx];
-    xiy = gy[(pt / NQ) % NQY];
-    qz = pt / (NQ * NQY);
-    xiz = pts[qz];
-  } else {
-    int f = 0, o = NPTS;
-    while (pt >= o + psi_face_points(NQ, NQY, f / 2)) {
-      o += psi_face_points(NQ, NQY, f / 2);
-      ++f;
-    }
-    const int d = f / 2, s = f % 2, k = pt - o;
-    const int Q1 = d == 0 ? NQY : NQ;  // first tangential direction: y for x-faces, x otherwise
-    const int q1 = k % Q1, q2 = k / Q1;
-    if (d == 0) {
-      qx = s ? NQ - 1 : 0;
-      xix = (double)s;
-      xiy = gy[q1];
-      qz = q2;
-      xiz = pts[q2];
-    } else if (d == 1) {
-      qx = q1;
-      xix = pts[q1];
-      xiy = (double)s;
-      qz = q2;
-      xiz = pts[q2];
-    } else {
-      qx = q1;
-      xix = pts[q1];
-      xiy = gy[q2];
-      qz = s ? NQ - 1 : 0;
-      xiz = (double)s;
-    }
+    r.qx = pt % NQ;
+    r.xix = pts[r.qx];
+    r.xiy = gy[(pt / NQ) % NQY];
+    r.qz = pt / (NQ * NQY);
+    r.xiz = pts[r.qz];
+    return r;
   }
-  double yh, gyh[3];
-  if (!geo) {
-    const double y = eta[ey] + (eta[ey + 1] - eta[ey]) * xiy;
-    yh = lower ? y + 1.0 : 1.0 - y;
-    gyh[0] = 0.0;
-    gyh[1] = lower ? 1.0 : -1.0;
-    gyh[2] = 0.0;
+  int f = 0, o = NPTS;
+  while (pt >= o + psi_face_points(NQ, NQY, f / 2)) {
+    o += psi_face_points(NQ, NQY, f / 2);
+    ++f;
+  }
+  const int d = f / 2, s = f % 2, k = pt - o;
+  const int Q1 = d == 0 ? NQY : NQ;  // first tangential direction: y for x-faces, x otherwise
+  const int q1 = k % Q1, q2 = k / Q1;
+  if (d == 0) {
+    r.qx = s ? NQ - 1 : 0;
+    r.xix = (double)s;
+    r.xiy = gy[q1];
+    r.qz = q2;
+    r.xiz = pts[q2];
+  } else if (d == 1) {
+    r.qx = q1;
+    r.xix = pts[q1];
+    r.xiy = (double)s;
+    r.qz = q2;
+    r.xiz = pts[q2];
   } else {
-    const double d00 = lower ? 0.0 : wdist[nx + 1 + ex], d10 = lower ? 0.0 : wdist[nx + 1 + ex + 1];
-    const double d01 = lower ? wdist[ex] : 0.0, d11 = lower ? wdist[ex + 1] : 0.0;
-    const double bot = (1.0 - xix) * d00 + xix * d10, top = (1.0 - xix) * d01 + xix * d11;
-    yh = (1.0 - xiy) * bot + xiy * top;
-    const double gx = (1.0 - xiy) * (d10 - d00) + xiy * (d11 - d01), gyy = top - bot;
-    const int64_t e = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
-    const double* Ji = geo + (e * geo_stride + pt) * 10;
+    r.qx = q1;
+    r.xix = pts[q1];
+    r.xiy = gy[q2];
+    r.qz = s ? NQ - 1 : 0;
+    r.xiz = (double)s;
+  }
+  return r;
+}
+
+// Wall distance y_h at the point and, when gyh != nullptr, its physical
+// gradient.  Curved lower wall: y_h is the bilinear (x, eta) interpolation
+// of the vertex distances to the closest wall vertex (wdist: rows iy = 1 and
+// iy = ny-1; the wall rows are 0), grad y_h = J^{-T} grad_xi y_h with J^{-1}
+// from the geometry table at the same point (index pt).
+__device__ __forceinline__ double wall_distance(const PsiArgs& A, const CellRef& c, const PointRef& p, int pt,
+                                                double* gyh) {
+  if (!A.geo) {
+    const double y = A.eta[c.ey] + (A.eta[c.ey + 1] - A.eta[c.ey]) * p.xiy;
+    if (gyh) {
+      gyh[0] = 0.0;
+      gyh[1] = c.lower ? 1.0 : -1.0;
+      gyh[2] = 0.0;
+    }
+    return c.lower ? y + 1.0 : 1.0 - y;
+  }
+  const int nx = A.nx, ex = c.ex;
+  const double d00 = c.lower ? 0.0 : A.wdist[nx + 1 + ex], d10 = c.lower ? 0.0 : A.wdist[nx + 1 + ex + 1];
+  const double d01 = c.lower ? A.wdist[ex] : 0.0, d11 = c.lower ? A.wdist[ex + 1] : 0.0;
+  const double bot = (1.0 - p.xix) * d00 + p.xix * d10, top = (1.0 - p.xix) * d01 + p.xix * d11;
+  if (gyh) {
+    const double gx = (1.0 - p.xiy) * (d10 - d00) + p.xiy * (d11 - d01), gyy = top - bot;
+    const int64_t e = ex + (int64_t)nx * (c.ey + (int64_t)A.ny * c.ez);
+    const double* Ji = A.geo + (e * A.geo_stride + pt) * 10;
     for (int dd = 0; dd < 3; ++dd) gyh[dd] = gx * Ji[0 * 3 + dd] + gyy * Ji[1 * 3 + dd];
   }
-  const int w = lower ? 0 : 1;
-  double tw, gtx = 0.0, gtz = 0.0;
-  if (tau_nodes) {
-    // wall vertices (ex, ez) .. (ex+1, ez+1) on the periodic vertex grid
-    const double* tn = tau_nodes + (int64_t)w * nz * nx;
-    const int jx = ex + 1 == nx ? 0 : ex + 1, jz = ez + 1 == nz ? 0 : ez + 1;
-    const double t00 = tn[(int64_t)ez * nx + ex], t10 = tn[(int64_t)ez * nx + jx];
-    const double t01 = tn[(int64_t)jz * nx + ex], t11 = tn[(int64_t)jz * nx + jx];
-    tw = (1.0 - xiz) * ((1.0 - xix) * t00 + xix * t10) + xiz * ((1.0 - xix) * t01 + xix * t11);
-    gtx = ((1.0 - xiz) * (t10 - t00) + xiz * (t11 - t01)) / hx;
-    gtz = ((1.0 - xix) * (t01 - t00) + xix * (t11 - t10)) / hz;
-  } else {
-    tw = tau[(((int64_t)w * nz + ez) * nx + ex) * NQ * NQ + (int64_t)qz * NQ + qx];
+  return (1.0 - p.xiy) * bot + p.xiy * top;
+}
+
+// tau_w at the point: the nearest Gauss column of the per-point field (zero
+// gradient), or the bilinear interpolation of the nodal field of the cell's
+// four wall vertices (periodic vertex grid) with its gradient (gtx, gtz).
+__device__ __forceinline__ double wall_tau(const PsiArgs& A, const CellRef& c, const PointRef& p, int NQ,
+                                           double& gtx, double& gtz) {
+  gtx = gtz = 0.0;
+  if (!A.tau_nodes)
+    return A.tau[(((int64_t)c.w * A.nz + c.ez) * A.nx + c.ex) * NQ * NQ + (int64_t)p.qz * NQ + p.qx];
+  const double* tn = A.tau_nodes + (int64_t)c.w * A.nz * A.nx;
+  const int jx = c.ex + 1 == A.nx ? 0 : c.ex + 1, jz = c.ez + 1 == A.nz ? 0 : c.ez + 1;
+  const double t00 = tn[(int64_t)c.ez * A.nx + c.ex], t10 = tn[(int64_t)c.ez * A.nx + jx];
+  const double t01 = tn[(int64_t)jz * A.nx + c.ex], t11 = tn[(int64_t)jz * A.nx + jx];
+  gtx = ((1.0 - p.xiz) * (t10 - t00) + p.xiz * (t11 - t01)) / A.hx;
+  gtz = ((1.0 - p.xix) * (t01 - t00) + p.xix * (t11 - t10)) / A.hz;
+  return (1.0 - p.xiz) * ((1.0 - p.xix) * t00 + p.xix * t10) + p.xiz * ((1.0 - p.xix) * t01 + p.xix * t11);
+}
+
+// Switch-off rule (Sec. 3.2): the enrichment of a wall cell stays on while at
+// least one point of its volume rule has y+ = y_h sqrt(tau_w)/nu >= yplus_off.
+// One 64-lane workgroup per enriched cell, the points spread over the lanes.
+template <int NQ, int NQY>
+__global__ __launch_bounds__(64) void activity_kernel(const PsiArgs A) {
+  constexpr int NPTS = NQ * NQY * NQ;
+  const int64_t enr = blockIdx.x;
+  const CellRef c = enriched_cell(A, enr);
+  int on = 0;
+  for (int pt = threadIdx.x; pt < NPTS; pt += 64) {
+    const PointRef p = decode_point<NQ, NQY>(pt, A.pts);
+    double gtx, gtz;
+    const double yh = wall_distance(A, c, p, pt, nullptr);
+    const double tw = wall_tau(A, c, p, NQ, gtx, gtz);
+    if (yh * sqrt(tw) / A.nu >= A.yplus_off) on = 1;
   }
-  double* o = psi + gid * 4;
+  on = __syncthreads_or(on);
+  if (threadIdx.x == 0) A.act[enr] = on;
+}
+
+// psi, grad psi at every point of the tables; zeros in switched-off cells.
+template <int NQ, int NQY>
+__global__ void psi_kernel(const PsiArgs A) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= A.nenr * A.psi_pts) return;
+  const int64_t enr = gid / A.psi_pts;
+  const int pt = (int)(gid - enr * A.psi_pts);
+  double* o = A.psi + gid * 4;
+  if (!A.act[enr]) {
+    o[0] = o[1] = o[2] = o[3] = 0.0;
+    return;
+  }
+  const CellRef c = enriched_cell(A, enr);
+  const PointRef p = decode_point<NQ, NQY>(pt, A.pts);
+  double gyh[3], gtx, gtz;
+  const double yh = wall_distance(A, c, p, pt, gyh);
+  const double tw = wall_tau(A, c, p, NQ, gtx, gtz);
   if (!(tw > 0.0) || !isfinite(tw)) {
     o[0] = o[1] = o[2] = o[3] = __builtin_nan("");
     return;
   }
+  const double nu = A.nu;
   const double st = sqrt(tw) / nu;
   double U, dU;
-  if (psi_kind == DG_PSI_VANDRIEST)
-    vandriest_eval(fmax(yh, 0.0) * st, kappa, A_plus, vd, U, dU);
+  if (A.psi_kind == DG_PSI_VANDRIEST)
+    vandriest_eval(fmax(yh, 0.0) * st, A.kappa, A.A_plus, A.vd, U, dU);
   else
-    spalding_root(fmax(yh, 0.0) * st, kappa, B, U, dU);
+    spalding_root(fmax(yh, 0.0) * st, A.kappa, A.B, U, dU);
   // y+ depends on tau_w through sqrt(tau_w): d y+/d tau_w = y_h / (2 nu sqrt(tau_w))
   const double dt = yh / (2.0 * nu * sqrt(tw));
   o[0] = U;
@@ -190,18 +267,44 @@ __global__ void psi_kernel(int nx, int ny, int nz, int lower_slot, int nslots, c
 
 int launch_psi(const dg_mesh* m, hipStream_t s) {
   if (m->nenr == 0) return DG_OK;
+  PsiArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  A.geo_stride = m->geo_stride;
+  A.psi_kind = m->P.psi_kind;
+  A.nenr = m->nenr;
+  A.eta = m->eta;
   // the Gauss points of both rules, contiguous, right after the tables
-  const double* pts = m->tab_u + tab_layout(m->np_u, m->P.nq_u, m->P.nq_wn).size;
+  A.pts = m->tab_u + tab_layout(m->np_u, m->P.nq_u, m->P.nq_wn).size;
+  A.tau = m->tau;
+  A.tau_nodes = m->tau_nodal ? m->tau_nodes : nullptr;
+  A.geo = m->geo;
+  A.wdist = m->wdist;
+  A.nu = m->P.nu;
+  A.kappa = m->P.kappa;
+  A.B = m->P.B;
+  A.A_plus = m->P.A_plus;
+  A.hx = m->hx;
+  A.hz = m->hz;
+  A.yplus_off = m->P.yplus_off;
+  A.psi = m->psi;
+  A.act = m->act;
+  A.vd = m->vd;
   const int64_t n = m->nenr * m->psi_pts;
   const unsigned nb = (unsigned)((n + 127) / 128);
-  const int lower_slot = m->lower_slot;
-#define X(a, b)                                                                                              \
-  if (m->P.nq_u == a && m->P.nq_wn == b) {                                                                   \
-    hipLaunchKernelGGL((psi_kernel<a, b>), dim3(nb), dim3(128), 0, s, m->P.nx, m->P.ny, m->P.nz, lower_slot, \
-                       m->n_enr_layers, m->eta, pts, m->tau, m->P.nu, m->P.kappa, m->P.B, m->nenr,          \
-                       m->psi_pts, m->psi, m->geo, m->geo_stride, m->wdist, m->P.psi_kind, m->P.A_plus,      \
-                       m->vd, m->tau_nodal ? m->tau_nodes : nullptr, m->hx, m->hz);                          \
-    return check_hip(hipGetLastError(), "psi kernel launch");                                                \
+#define X(a, b)                                                                            \
+  if (m->P.nq_u == a && m->P.nq_wn == b) {                                                 \
+    if (A.yplus_off > 0.0) {                                                               \
+      hipLaunchKernelGGL((activity_kernel<a, b>), dim3((unsigned)m->nenr), dim3(64), 0, s, A); \
+      int rc = check_hip(hipGetLastError(), "enrichment activity kernel launch");         \
+      if (rc) return rc;                                                                   \
+    }                                                                                      \
+    hipLaunchKernelGGL((psi_kernel<a, b>), dim3(nb), dim3(128), 0, s, A);                  \
+    return check_hip(hipGetLastError(), "psi kernel launch");                              \
   }
   DG_PSI_COMBOS(X)
 #undef X
