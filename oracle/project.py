@@ -1,5 +1,5 @@
 """Cell-wise L2 projection onto the refreshed enriched space (arXiv
-1705.08813, Sec. 3.2, eq. l2).
+1705.08813, Sec. 3.2, eq. l2), and the inverse of the velocity mass matrix.
 
 TEST INFRASTRUCTURE ONLY (never used by the product).
 
@@ -95,3 +95,48 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
             u_new[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = x[:n3]
             u_new[off + 3 * k + c] = x[n3] if on else 0.0
     return (u_new, conds) if return_cond else u_new
+
+
+def inverse_mass(cfg, r, psi):
+    """x = M^{-1} r for the velocity mass matrix of every cell (the operator
+    of the semi-discrete system M du/dt = -R(u), Sec. 4.1-4.2): per cell and
+    component M_ij = (phi_i, phi_j)_e with phi the cell's local basis (N_B,
+    plus psi in an enriched cell whose enrichment is on) and the cell's own
+    quadrature rule (nq_u^3, or nq_u x nq_wn x nq_u in enriched cells),
+    assembled directly from 3-D basis values and solved densely.  psi:
+    [nenr][npts] values at the enriched volume rule (zero rows: enrichment
+    switched off, its unknowns set to 0).  Flat (box) meshes only."""
+    if cfg.wall_amp != 0.0:
+        raise ValueError("flat meshes only")
+    n3 = (cfg.k_u + 1) ** 3
+    r = np.asarray(r, dtype=np.float64)
+    x = np.zeros_like(r)
+    eta = vertex_eta(cfg)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    off = cfg.ncell * 3 * n3
+    enr = {int(e): k for k, e in enumerate(enriched_cells(cfg))}
+    pts_e, wts_e = volume_rule(cfg)
+    V_e = basis_at(cfg, pts_e)
+    pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
+    V_r = basis_at(cfg, pts_r)
+    M_reg = V_r.T @ (wts_r[:, None] * V_r)
+    for e in range(cfg.ncell):
+        ey = (e // cfg.nx) % cfg.ny
+        detJ = hx * (eta[ey + 1] - eta[ey]) * hz
+        k = enr.get(e)
+        if k is None:
+            M = detJ * M_reg
+        else:
+            ps = np.asarray(psi[k], dtype=float)
+            on = bool(np.any(ps != 0.0))
+            Phi = np.hstack([V_e, ps[:, None]]) if on else V_e
+            M = Phi.T @ ((detJ * wts_e)[:, None] * Phi)
+        for c in range(3):
+            rp = r[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
+            if k is not None and M.shape[0] == n3 + 1:
+                sol = np.linalg.solve(M, np.concatenate([rp, [r[off + 3 * k + c]]]))
+                x[off + 3 * k + c] = sol[n3]
+                x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = sol[:n3]
+            else:
+                x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = np.linalg.solve(M, rp)
+    return x
