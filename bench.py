@@ -314,7 +314,22 @@ def main():
                                 "refresh_with_switch_off_ms": ev4[0].elapsed_time(ev4[1]) / nrep,
                                 "project_ms": ev4[1].elapsed_time(ev4[2]) / nrep, "project_in_place_ms": t_in,
                                 "in_place_alg_bytes": prj_bytes, "in_place_GBps_alg": prj_bytes / (t_in * 1e-3) / 1e9}
-        del pm, un, uw, tnd
+        # inverse velocity mass matrix on the same (y+ ~ 100) space: 16 B per unknown (r in, x out)
+        xm = torch.empty_like(u)
+        for _ in range(3):
+            pm.apply_inverse_mass(u, xm)
+        ev5 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev5[0].record(stream)
+        for _ in range(nrep):
+            pm.apply_inverse_mass(u, xm)
+        ev5[1].record(stream)
+        torch.cuda.synchronize()
+        t_im = ev5[0].elapsed_time(ev5[1]) / nrep
+        im_bytes = 16.0 * pm.n_vel
+        extras["inverse_mass"] = {"unknowns": pm.n_vel, "ms": t_im, "alg_bytes": im_bytes,
+                                  "GBps_alg": im_bytes / (t_im * 1e-3) / 1e9,
+                                  "hbm_frac": im_bytes / (t_im * 1e-3) / 8e12}
+        del pm, un, uw, tnd, xm
     if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)

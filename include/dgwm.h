@@ -222,6 +222,22 @@ int64_t dg_batch_workspace_bytes(int32_t n);
 int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, dg_prec prec, const void* const* u,
                                        void* const* r, void* workspace, size_t ws_bytes, void* stream);
 
+/* Inverse of the velocity mass matrix, x = M^{-1} r, so that the
+ * semi-discrete momentum balance M du/dt = -R(u) of the residual above (paper
+ * Sec. 4.1-4.2) advances explicitly as du/dt = -M^{-1} R(u).  Per cell and
+ * component M_ij = (phi_i, phi_j)_e over the cell's local basis (N_B, plus psi
+ * in an enriched cell whose enrichment is on) with the cell's own quadrature
+ * rule (nq_u^3; nq_u x nq_wn x nq_u in enriched cells); the enrichment
+ * unknowns of a switched-off cell are set to 0.  Block-diagonal (cell-local):
+ * regular cells by the tensor product of inverse 1-D mass matrices, enriched
+ * cells by the Schur complement on the enrichment row.  The enriched blocks
+ * are ill-conditioned where psi is close to a polynomial on the cell (cond
+ * 1e6-1e8 at wall-cell tops of y+ 50-400), which bounds the attainable
+ * accuracy of any M^{-1} r there.
+ *   r, x: device, dg_num_dofs(mesh, 0) doubles; x may be r (in place).
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall), DG_ERR_HIP. */
+int dg_apply_inverse_mass(const dg_mesh* mesh, const double* r, double* x, void* stream);
+
 /* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
  * term, flux eq. ipflux) with homogeneous Neumann data on the walls:
  *   (A p)(q) = sum_e (grad q, grad p)_e + sum_{interior F} [ -1/2 (grad q.n)(p- - p+)

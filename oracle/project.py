@@ -97,7 +97,7 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
     return (u_new, conds) if return_cond else u_new
 
 
-def inverse_mass(cfg, r, psi):
+def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     """x = M^{-1} r for the velocity mass matrix of every cell (the operator
     of the semi-discrete system M du/dt = -R(u), Sec. 4.1-4.2): per cell and
     component M_ij = (phi_i, phi_j)_e with phi the cell's local basis (N_B,
@@ -105,7 +105,10 @@ def inverse_mass(cfg, r, psi):
     quadrature rule (nq_u^3, or nq_u x nq_wn x nq_u in enriched cells),
     assembled directly from 3-D basis values and solved densely.  psi:
     [nenr][npts] values at the enriched volume rule (zero rows: enrichment
-    switched off, its unknowns set to 0).  Flat (box) meshes only."""
+    switched off, its unknowns set to 0).  cells: the cells to invert (the
+    operator is block diagonal; the others are left at 0).  With return_cond,
+    also the 2-norm condition number of each cell's block (0 for cells not
+    inverted).  Flat (box) meshes only."""
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -120,7 +123,8 @@ def inverse_mass(cfg, r, psi):
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     V_r = basis_at(cfg, pts_r)
     M_reg = V_r.T @ (wts_r[:, None] * V_r)
-    for e in range(cfg.ncell):
+    conds = np.zeros(cfg.ncell)
+    for e in (range(cfg.ncell) if cells is None else [int(c) for c in cells]):
         ey = (e // cfg.nx) % cfg.ny
         detJ = hx * (eta[ey + 1] - eta[ey]) * hz
         k = enr.get(e)
@@ -131,6 +135,7 @@ def inverse_mass(cfg, r, psi):
             on = bool(np.any(ps != 0.0))
             Phi = np.hstack([V_e, ps[:, None]]) if on else V_e
             M = Phi.T @ ((detJ * wts_e)[:, None] * Phi)
+        conds[e] = np.linalg.cond(M)
         for c in range(3):
             rp = r[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
             if k is not None and M.shape[0] == n3 + 1:
@@ -139,4 +144,4 @@ def inverse_mass(cfg, r, psi):
                 x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = sol[:n3]
             else:
                 x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = np.linalg.solve(M, rp)
-    return x
+    return (x, conds) if return_cond else x

@@ -146,6 +146,16 @@ class Mesh:
         _lib.check(_lib.lib().dg_project_velocity(self.handle, _dptr(u_old), _dptr(u_new), _stream_ptr(stream)))
         return u_new
 
+    def apply_inverse_mass(self, r, x=None, stream=None):
+        """x = M^{-1} r with the velocity mass matrix (x may be r)."""
+        import torch
+        self._check_f64(r, self.n_vel, "r")
+        if x is None:
+            x = torch.empty_like(r)
+        self._check_f64(x, self.n_vel, "x")
+        _lib.check(_lib.lib().dg_apply_inverse_mass(self.handle, _dptr(r), _dptr(x), _stream_ptr(stream)))
+        return x
+
     def enrichment_active(self, stream=None):
         """Activity flags (int32 device tensor, 1 on / 0 switched off) of the
         enriched cells in the current space."""

@@ -214,6 +214,8 @@ size_t solve_bytes_mesh(const dg_mesh& m);
 // device data of the hierarchy (levels' heights and diagonals, coarse inverse)
 int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+// x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)
+int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s);
 // u_new = L2 projection of u_old from the space of psi_prev onto that of psi
 int launch_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, hipStream_t s);
 // nodal wall shear stress [wall][nz][nx] of the FP64 velocity u (flat walls)

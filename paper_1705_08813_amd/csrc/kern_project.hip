@@ -44,15 +44,16 @@ struct ProjArgs {
   double* u_new;            // may equal u_old
 };
 
-// out[c][...] = sum_l A[o][l] in[c][...] along one direction of a 3-D array
-// stored with strides (1, E0, E0 E1); E = extents of `in`, MO = output extent
-// along DIR; A is [MO][L] with row stride L (A^T when TR: A[l][o]).
-template <int DIR, int E0, int E1, int E2, int MO, bool TR>
-__device__ __forceinline__ void sweep2(const double* in, double* out, const double* A, int tid) {
+// out[c][...] = sum_l A[o][l] in[c][...] along one direction of NC stacked
+// 3-D arrays stored with strides (1, E0, E0 E1); E = extents of `in`, MO =
+// output extent along DIR; A is [MO][L] with row stride L (A^T when TR:
+// A[l][o]).  NT threads share the work.
+template <int NC, int DIR, int E0, int E1, int E2, int MO, bool TR, int NT = kPrjThreads>
+__device__ __forceinline__ void sweepn(const double* in, double* out, const double* A, int tid) {
   constexpr int L = DIR == 0 ? E0 : DIR == 1 ? E1 : E2;
   constexpr int O0 = DIR == 0 ? MO : E0, O1 = DIR == 1 ? MO : E1, O2 = DIR == 2 ? MO : E2;
   constexpr int NI = E0 * E1 * E2, NO = O0 * O1 * O2;
-  for (int it = tid; it < 2 * NO; it += kPrjThreads) {
+  for (int it = tid; it < NC * NO; it += NT) {
     const int c = it / NO, r = it - c * NO;
     const int o0 = r % O0, o1 = (r / O0) % O1, o2 = r / (O0 * O1);
     const int o = DIR == 0 ? o0 : DIR == 1 ? o1 : o2;
@@ -66,106 +67,267 @@ __device__ __forceinline__ void sweep2(const double* in, double* out, const doub
   }
 }
 
+// 1-D tables of an enriched cell in LDS: S of the wall-parallel and of the
+// wall-normal rule, their weights, the inverse 1-D mass matrices.
 template <int NP, int NQ, int NQY>
-__global__ __launch_bounds__(kPrjThreads) void project_kernel(const ProjArgs A) {
-  constexpr int NPT = NQ * NQY * NQ, NP3 = NP * NP * NP;
-  constexpr TabLayout TL = tab_layout(NP, NQ, NQY);
-  __shared__ double sS[NQ * NP], sSy[NQY * NP], sW[NQ], sWy[NQY], sMi[NP * NP], sMiy[NP * NP];
-  __shared__ double ps[2 * NPT];        // psi (old, new) at the points, later r = psi - P psi
-  __shared__ double f[2 * NPT];         // w_q psi
-  __shared__ double t1[2 * NQ * NQY * NP];
-  __shared__ double t2[2 * NQ * NP * NP];
-  __shared__ double a[2 * NP3], b[2 * NP3];
-  __shared__ double red[2 * (kPrjThreads / 64)];
-  __shared__ double sut[3];                 // u~_old (read before any write: u_new may be u_old)
-  const int tid = threadIdx.x;
-  const int64_t enr = blockIdx.x;
-  const int ex = (int)(enr % A.nx);
-  const int64_t t0 = enr / A.nx;
-  const int slot = (int)(t0 % A.nslots);
-  const int ez = (int)(t0 / A.nslots);
-  const int ey = slot == A.lower_slot ? 0 : A.ny - 1;
-  const int64_t e = ex + (int64_t)A.nx * (ey + (int64_t)A.ny * ez);
+struct Tab1d {
+  double S[NQ * NP], Sy[NQY * NP], W[NQ], Wy[NQY], Mi[NP * NP], Miy[NP * NP];
+};
 
-  for (int i = tid; i < NQ * NP; i += kPrjThreads) sS[i] = A.tab[TL.S + i];
-  for (int i = tid; i < NQY * NP; i += kPrjThreads) sSy[i] = A.tab[TL.Sy + i];
+template <int NP, int NQ, int NQY>
+__device__ __forceinline__ void load_tab1d(const double* tab, const double* minv, Tab1d<NP, NQ, NQY>& T, int tid) {
+  constexpr TabLayout TL = tab_layout(NP, NQ, NQY);
+  for (int i = tid; i < NQ * NP; i += kPrjThreads) T.S[i] = tab[TL.S + i];
+  for (int i = tid; i < NQY * NP; i += kPrjThreads) T.Sy[i] = tab[TL.Sy + i];
   for (int i = tid; i < NP * NP; i += kPrjThreads) {
-    sMi[i] = A.minv[i];
-    sMiy[i] = A.minv[NP * NP + i];
+    T.Mi[i] = minv[i];
+    T.Miy[i] = minv[NP * NP + i];
   }
-  if (tid < NQ) sW[tid] = A.tab[TL.w + tid];
-  if (tid < NQY) sWy[tid] = A.tab[TL.wy + tid];
-  __syncthreads();
-  // volume points q = qx + NQ (qy + NQY qz) are the first NPT entries of a cell's table
-  const double* po = A.psi_old + enr * A.psi_pts * 4;
-  const double* pn = A.psi_new + enr * A.psi_pts * 4;
+  if (tid < NQ) T.W[tid] = tab[TL.w + tid];
+  if (tid < NQY) T.Wy[tid] = tab[TL.wy + tid];
+}
+
+// LDS work arrays of the polynomial part of NC <= 2 enrichment functions.
+template <int NP, int NQ, int NQY>
+struct PsiPoly {
+  static constexpr int NPT = NQ * NQY * NQ, NP3 = NP * NP * NP;
+  double r[2 * NPT];   // psi at the volume points, then r = psi - P psi
+  double f[2 * NPT];
+  double t1[2 * NQ * NQY * NP];
+  double t2[2 * NQ * NP * NP];
+  double a[2 * NP3];
+  double b[2 * NP3];   // coefficients of P psi (nodal basis)
+};
+
+// For the NC tables psi[c] (entry 0 of [pt][4], volume points first, q = qx +
+// NQ (qy + NQY qz)) of one cell: b[c] = K^{-1} (N, psi_c)_w, the nodal
+// coefficients of the L2 projection P psi_c onto the cell's polynomials (K
+// the weighted 1-D mass matrices' tensor product, |det J| cancels), and
+// r[c] = psi_c - P psi_c at the points.  Ends with a barrier.
+template <int NC, int NP, int NQ, int NQY>
+__device__ __forceinline__ void psi_poly_part(const double* const* psi, const Tab1d<NP, NQ, NQY>& T,
+                                              PsiPoly<NP, NQ, NQY>& L, int tid) {
+  constexpr int NPT = NQ * NQY * NQ;
   for (int q = tid; q < NPT; q += kPrjThreads) {
     const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
-    const double w = sW[qx] * sWy[qy] * sW[qz];
-    const double vo = po[q * 4], vn = pn[q * 4];
-    ps[q] = vo;
-    ps[NPT + q] = vn;
-    f[q] = w * vo;
-    f[NPT + q] = w * vn;
+    const double w = T.W[qx] * T.Wy[qy] * T.W[qz];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double v = psi[c][q * 4];
+      L.r[c * NPT + q] = v;
+      L.f[c * NPT + q] = w * v;
+    }
   }
   __syncthreads();
   // (N_B, psi) = S^T W psi, one sweep per direction
-  sweep2<0, NQ, NQY, NQ, NP, true>(f, t1, sS, tid);     // [c][qz][qy][i]
+  sweepn<NC, 0, NQ, NQY, NQ, NP, true>(L.f, L.t1, T.S, tid);     // [c][qz][qy][i]
   __syncthreads();
-  sweep2<1, NP, NQY, NQ, NP, true>(t1, t2, sSy, tid);   // [c][qz][j][i]
+  sweepn<NC, 1, NP, NQY, NQ, NP, true>(L.t1, L.t2, T.Sy, tid);   // [c][qz][j][i]
   __syncthreads();
-  sweep2<2, NP, NP, NQ, NP, true>(t2, a, sS, tid);      // [c][k][j][i]
+  sweepn<NC, 2, NP, NP, NQ, NP, true>(L.t2, L.a, T.S, tid);      // [c][k][j][i]
   __syncthreads();
-  // a = M^{-1} (N, psi) with M^{-1} = Mz^{-1} (x) My^{-1} (x) Mx^{-1}
-  sweep2<0, NP, NP, NP, NP, false>(a, b, sMi, tid);
+  // K^{-1} = Kz^{-1} (x) Ky^{-1} (x) Kx^{-1}
+  sweepn<NC, 0, NP, NP, NP, NP, false>(L.a, L.b, T.Mi, tid);
   __syncthreads();
-  sweep2<1, NP, NP, NP, NP, false>(b, a, sMiy, tid);
+  sweepn<NC, 1, NP, NP, NP, NP, false>(L.b, L.a, T.Miy, tid);
   __syncthreads();
-  sweep2<2, NP, NP, NP, NP, false>(a, b, sMi, tid);
+  sweepn<NC, 2, NP, NP, NP, NP, false>(L.a, L.b, T.Mi, tid);
   __syncthreads();
   // P psi at the points: interpolate b back
-  sweep2<0, NP, NP, NP, NQ, false>(b, t2, sS, tid);     // [c][k][j][qx]
+  sweepn<NC, 0, NP, NP, NP, NQ, false>(L.b, L.t2, T.S, tid);     // [c][k][j][qx]
   __syncthreads();
-  sweep2<1, NQ, NP, NP, NQY, false>(t2, t1, sSy, tid);  // [c][k][qy][qx]
+  sweepn<NC, 1, NQ, NP, NP, NQY, false>(L.t2, L.t1, T.Sy, tid);  // [c][k][qy][qx]
   __syncthreads();
-  sweep2<2, NQ, NQY, NP, NQ, false>(t1, f, sS, tid);    // [c][qz][qy][qx]
+  sweepn<NC, 2, NQ, NQY, NP, NQ, false>(L.t1, L.f, T.S, tid);    // [c][qz][qy][qx]
   __syncthreads();
-  // r = psi - P psi, then (r_new, r_old) and (r_new, r_new)
-  double num = 0.0, den = 0.0;
+  for (int q = tid; q < NC * NPT; q += kPrjThreads) L.r[q] -= L.f[q];
+  __syncthreads();
+}
+
+// Block sum of NV values per thread (fixed order: lanes, then wavefronts).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red, int tid) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_down(v[i], off, 64);
+  constexpr int NW = kPrjThreads / 64;
+  __syncthreads();
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[i * NW + (tid >> 6)] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    v[i] = 0.0;
+    for (int wv = 0; wv < NW; ++wv) v[i] += red[i * NW + wv];
+  }
+}
+
+__device__ __forceinline__ int64_t enriched_cell_index(int nx, int ny, int lower_slot, int nslots, int64_t enr) {
+  const int ex = (int)(enr % nx);
+  const int64_t t0 = enr / nx;
+  const int slot = (int)(t0 % nslots);
+  const int ez = (int)(t0 / nslots);
+  const int ey = slot == lower_slot ? 0 : ny - 1;
+  return ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+}
+
+template <int NP, int NQ, int NQY>
+__global__ __launch_bounds__(kPrjThreads) void project_kernel(const ProjArgs A) {
+  constexpr int NPT = NQ * NQY * NQ, NP3 = NP * NP * NP;
+  __shared__ Tab1d<NP, NQ, NQY> T;
+  __shared__ PsiPoly<NP, NQ, NQY> L;
+  __shared__ double red[2 * (kPrjThreads / 64)];
+  __shared__ double sut[3];  // u~_old (read before any write: u_new may be u_old)
+  const int tid = threadIdx.x;
+  const int64_t enr = blockIdx.x;
+  const int64_t e = enriched_cell_index(A.nx, A.ny, A.lower_slot, A.nslots, enr);
+  load_tab1d<NP, NQ, NQY>(A.tab, A.minv, T, tid);
+  __syncthreads();
+  const double* psi[2] = {A.psi_old + enr * A.psi_pts * 4, A.psi_new + enr * A.psi_pts * 4};
+  psi_poly_part<2, NP, NQ, NQY>(psi, T, L, tid);
+  // (r_new, r_old) and (r_new, r_new)
+  double v[2] = {0.0, 0.0};
   for (int q = tid; q < NPT; q += kPrjThreads) {
     const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
-    const double w = sW[qx] * sWy[qy] * sW[qz];
-    const double ro = ps[q] - f[q], rn = ps[NPT + q] - f[NPT + q];
-    num += w * rn * ro;
-    den += w * rn * rn;
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    num += __shfl_down(num, off, 64);
-    den += __shfl_down(den, off, 64);
-  }
-  if ((tid & 63) == 0) {
-    red[tid >> 6] = num;
-    red[kPrjThreads / 64 + (tid >> 6)] = den;
+    const double w = T.W[qx] * T.Wy[qy] * T.W[qz];
+    const double ro = L.r[q], rn = L.r[NPT + q];
+    v[0] += w * rn * ro;
+    v[1] += w * rn * rn;
   }
   const int64_t eo = A.ncell * 3 * NP3 + enr * 3;  // enrichment unknowns of the cell
   if (tid < 3) sut[tid] = A.u_old[eo + tid];
-  __syncthreads();
-  num = den = 0.0;
-  for (int wv = 0; wv < kPrjThreads / 64; ++wv) {
-    num += red[wv];
-    den += red[kPrjThreads / 64 + wv];
-  }
-  const double ratio = (A.act_new[enr] && den > 0.0) ? num / den : 0.0;
+  block_sum<2>(v, red, tid);
+  const double ratio = (A.act_new[enr] && v[1] > 0.0) ? v[0] / v[1] : 0.0;
   // each entry is read and written by the same thread, so u_new may alias u_old
   const double* ub = A.u_old + e * 3 * NP3;
   double* vb = A.u_new + e * 3 * NP3;
   for (int it = tid; it < 3 * NP3; it += kPrjThreads) {
     const int c = it / NP3, B = it - c * NP3;
     const double uto = sut[c];
-    vb[it] = ub[it] + uto * b[B] - ratio * uto * b[NP3 + B];
+    vb[it] = ub[it] + uto * L.b[B] - ratio * uto * L.b[NP3 + B];
   }
   if (tid < 3) A.u_new[eo + tid] = ratio * sut[tid];
+}
+
+// ---------------------------------------------------------------------------
+// Inverse velocity mass matrix, x = M^{-1} r (M du/dt = -R(u)).
+//
+// Regular cell: M = |det J| Kz (x) Ky (x) Kx per component with the cell's
+// nq^3 rule, so x = |det J|^{-1} (Kz^{-1} (x) Ky^{-1} (x) Kx^{-1}) r: three
+// sweeps through LDS, HBM-bound (16 B per unknown).
+// Enriched cell (local basis N_B and psi, rule nq x nqy x nq): with
+// K = the polynomial block / |det J|, a = K^{-1} (N, psi)_w and
+// s = |det J| (r_psi, r_psi)_w (r_psi = psi - P psi), the Schur complement on
+// the enrichment row gives
+//   x~ = (r~ - a . r_bar) / s,   x_bar = |det J|^{-1} K^{-1} r_bar - a x~;
+// a cell whose enrichment is switched off gets x~ = 0.
+
+struct InvMassArgs {
+  int nx, ny, nz, lower_slot, nslots, psi_pts, layer_lo, nlayers;
+  int64_t ncell;
+  double ihx, ihz;
+  const double* ihy;      // reciprocal cell heights
+  const double* tab;
+  const double* minv;
+  const double* psi;
+  const int32_t* act;
+  const double* r;
+  double* x;
+};
+
+constexpr int kImThreads = 128;
+
+// Regular cells: block b = ex + nx (ly + nlayers ez), ey = layer_lo + ly.
+template <int NP>
+__global__ __launch_bounds__(kImThreads) void invmass_regular_kernel(const InvMassArgs A) {
+  constexpr int NP3 = NP * NP * NP;
+  __shared__ double Mi[NP * NP];
+  __shared__ double u0[3 * NP3], u1[3 * NP3];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int ex = (int)(b % A.nx);
+  const int64_t t0 = b / A.nx;
+  const int ly = (int)(t0 % A.nlayers);
+  const int ez = (int)(t0 / A.nlayers);
+  const int ey = A.layer_lo + ly;
+  const int64_t e = ex + (int64_t)A.nx * (ey + (int64_t)A.ny * ez);
+  for (int i = tid; i < NP * NP; i += kImThreads) Mi[i] = A.minv[i];
+  const double* re = A.r + e * 3 * NP3;
+  for (int i = tid; i < 3 * NP3; i += kImThreads) u0[i] = re[i];
+  __syncthreads();
+  sweepn<3, 0, NP, NP, NP, NP, false, kImThreads>(u0, u1, Mi, tid);
+  __syncthreads();
+  sweepn<3, 1, NP, NP, NP, NP, false, kImThreads>(u1, u0, Mi, tid);
+  __syncthreads();
+  const double idet = A.ihx * A.ihy[ey] * A.ihz;
+  double* xe = A.x + e * 3 * NP3;
+  // last sweep (z) straight to memory
+  constexpr int NO = NP3;
+  for (int it = tid; it < 3 * NO; it += kImThreads) {
+    const int c = it / NO, rr = it - c * NO;
+    const int o2 = rr / (NP * NP), base = rr - o2 * NP * NP;
+    const double* ip = u0 + c * NP3 + base;
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) s += Mi[o2 * NP + l] * ip[l * NP * NP];
+    xe[it] = s * idet;
+  }
+}
+
+template <int NP, int NQ, int NQY>
+__global__ __launch_bounds__(kPrjThreads) void invmass_enriched_kernel(const InvMassArgs A) {
+  constexpr int NPT = NQ * NQY * NQ, NP3 = NP * NP * NP;
+  __shared__ Tab1d<NP, NQ, NQY> T;
+  __shared__ PsiPoly<NP, NQ, NQY> L;
+  __shared__ double rp[3 * NP3], y0[3 * NP3], y1[3 * NP3];
+  __shared__ double red[4 * (kPrjThreads / 64)];
+  __shared__ double sre[3];
+  const int tid = threadIdx.x;
+  const int64_t enr = blockIdx.x;
+  const int64_t e = enriched_cell_index(A.nx, A.ny, A.lower_slot, A.nslots, enr);
+  const int ey = (int)((e / A.nx) % A.ny);
+  load_tab1d<NP, NQ, NQY>(A.tab, A.minv, T, tid);
+  const double* re = A.r + e * 3 * NP3;
+  for (int i = tid; i < 3 * NP3; i += kPrjThreads) rp[i] = re[i];
+  const int64_t eo = A.ncell * 3 * NP3 + enr * 3;
+  if (tid < 3) sre[tid] = A.r[eo + tid];
+  __syncthreads();
+  const double* psi[1] = {A.psi + enr * A.psi_pts * 4};
+  psi_poly_part<1, NP, NQ, NQY>(psi, T, L, tid);
+  // K^{-1} r_bar, three components
+  sweepn<3, 0, NP, NP, NP, NP, false>(rp, y0, T.Mi, tid);
+  __syncthreads();
+  sweepn<3, 1, NP, NP, NP, NP, false>(y0, y1, T.Miy, tid);
+  __syncthreads();
+  sweepn<3, 2, NP, NP, NP, NP, false>(y1, y0, T.Mi, tid);
+  // (r_psi, r_psi)_w and a . r_bar_c
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int q = tid; q < NPT; q += kPrjThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+    const double w = T.W[qx] * T.Wy[qy] * T.W[qz];
+    v[0] += w * L.r[q] * L.r[q];
+  }
+  for (int B = tid; B < NP3; B += kPrjThreads) {
+    const double ab = L.b[B];
+    v[1] += ab * rp[B];
+    v[2] += ab * rp[NP3 + B];
+    v[3] += ab * rp[2 * NP3 + B];
+  }
+  block_sum<4>(v, red, tid);   // (its barriers also order the last sweep before the reads below)
+  const double idet = A.ihx * A.ihy[ey] * A.ihz;
+  const bool on = A.act[enr] && v[0] > 0.0;
+  const double is = on ? idet / v[0] : 0.0;
+  double xt[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xt[c] = (sre[c] - v[1 + c]) * is;
+  double* xe = A.x + e * 3 * NP3;
+  for (int it = tid; it < 3 * NP3; it += kPrjThreads) {
+    const int c = it / NP3, B = it - c * NP3;
+    xe[it] = y0[it] * idet - L.b[B] * xt[c];
+  }
+  if (tid < 3) A.x[eo + tid] = xt[tid];
 }
 
 }  // namespace
@@ -203,6 +365,51 @@ int launch_project_velocity(const dg_mesh* m, const double* u_old, double* u_new
   DG_PRJ_COMBOS(X)
 #undef X
   return set_error(DG_ERR_UNSUPPORTED, "projection: (k_u+1, nq_u, nq_wn) combination not compiled");
+}
+
+int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s) {
+  InvMassArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  // regular layers: all but the enriched wall-adjacent ones
+  A.layer_lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  A.nlayers = hi - A.layer_lo + 1;
+  A.ncell = m->ncell;
+  A.ihx = 1.0 / m->hx;
+  A.ihz = 1.0 / m->hz;
+  A.ihy = m->hy + m->P.ny;
+  A.tab = m->tab_u;
+  A.minv = m->minv;
+  A.psi = m->psi;
+  A.act = m->act;
+  A.r = r;
+  A.x = x;
+  const int64_t nreg = A.nlayers > 0 ? (int64_t)m->P.nx * A.nlayers * m->P.nz : 0;
+  bool done = nreg == 0;
+#define X(p)                                                                                               \
+  if (!done && m->np_u == p) {                                                                             \
+    hipLaunchKernelGGL((invmass_regular_kernel<p>), dim3((unsigned)nreg), dim3(kImThreads), 0, s, A);       \
+    const int rc = check_hip(hipGetLastError(), "inverse mass kernel launch");                             \
+    if (rc) return rc;                                                                                     \
+    done = true;                                                                                           \
+  }
+  X(3) X(4) X(5) X(6)
+#undef X
+  if (!done) return set_error(DG_ERR_UNSUPPORTED, "inverse mass: degree not compiled");
+  if (m->nenr == 0) return DG_OK;
+#define X(p, q, w)                                                                                          \
+  if (m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                                  \
+    hipLaunchKernelGGL((invmass_enriched_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
+    return check_hip(hipGetLastError(), "inverse mass kernel launch");                                      \
+  }
+  DG_PRJ_COMBOS(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "inverse mass: (k_u+1, nq_u, nq_wn) combination not compiled");
 }
 
 }  // namespace dgwm
