@@ -233,7 +233,10 @@ int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, 
  * cells by the Schur complement on the enrichment row.  The enriched blocks
  * are ill-conditioned where psi is close to a polynomial on the cell (cond
  * 1e6-1e8 at wall-cell tops of y+ 50-400), which bounds the attainable
- * accuracy of any M^{-1} r there.
+ * accuracy of any M^{-1} r there.  The first call after setup or after a
+ * wall-shear update also fills a per-mesh cache of the enriched cells'
+ * polynomial parts of psi on `stream`; a later call on another stream must be
+ * ordered after that one.
  *   r, x: device, dg_num_dofs(mesh, 0) doubles; x may be r (in place).
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall), DG_ERR_HIP. */
 int dg_apply_inverse_mass(const dg_mesh* mesh, const double* r, double* x, void* stream);

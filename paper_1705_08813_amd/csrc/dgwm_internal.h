@@ -153,6 +153,8 @@ struct dg_mesh {
   int32_t* act;           // [enr] enrichment on (1) or switched off (0)
   int32_t* act_prev;      // the same flags before the last wall-shear update
   double* minv;           // inverse 1-D mass matrices [2][np_u][np_u]: x/z rule, wall-normal rule
+  double* apoly;          // [enr][np_u^3 + 1]: polynomial part of the current psi (inverse mass cache)
+  mutable int apoly_ok = 0;  // apoly matches the current psi table
   double* diag;           // Poisson diagonal (FP64)
   float* diag32;          // Poisson diagonal (FP32 copy)
   double* hy;             // ny cell heights, then their ny reciprocals

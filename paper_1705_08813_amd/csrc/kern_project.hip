@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kPrjThreads) void project_kernel(const ProjArgs A) 
 // a cell whose enrichment is switched off gets x~ = 0.
 
 struct InvMassArgs {
-  int nx, ny, nz, lower_slot, nslots, psi_pts, layer_lo, nlayers;
+  int nx, ny, nz, lower_slot, upper_slot, nslots, psi_pts;
   int64_t ncell;
   double ihx, ihz;
   const double* ihy;      // reciprocal cell heights
@@ -233,101 +233,161 @@ struct InvMassArgs {
   const double* minv;
   const double* psi;
   const int32_t* act;
+  double* apoly;          // [enr][NP3 + 1]: a, then 1/(r_psi, r_psi)_w (0: enrichment off)
   const double* r;
   double* x;
 };
 
-constexpr int kImThreads = 128;
-
-// Regular cells: block b = ex + nx (ly + nlayers ez), ey = layer_lo + ly.
-template <int NP>
-__global__ __launch_bounds__(kImThreads) void invmass_regular_kernel(const InvMassArgs A) {
-  constexpr int NP3 = NP * NP * NP;
-  __shared__ double Mi[NP * NP];
-  __shared__ double u0[3 * NP3], u1[3 * NP3];
-  const int tid = threadIdx.x;
-  const int64_t b = blockIdx.x;
-  const int ex = (int)(b % A.nx);
-  const int64_t t0 = b / A.nx;
-  const int ly = (int)(t0 % A.nlayers);
-  const int ez = (int)(t0 / A.nlayers);
-  const int ey = A.layer_lo + ly;
-  const int64_t e = ex + (int64_t)A.nx * (ey + (int64_t)A.ny * ez);
-  for (int i = tid; i < NP * NP; i += kImThreads) Mi[i] = A.minv[i];
-  const double* re = A.r + e * 3 * NP3;
-  for (int i = tid; i < 3 * NP3; i += kImThreads) u0[i] = re[i];
-  __syncthreads();
-  sweepn<3, 0, NP, NP, NP, NP, false, kImThreads>(u0, u1, Mi, tid);
-  __syncthreads();
-  sweepn<3, 1, NP, NP, NP, NP, false, kImThreads>(u1, u0, Mi, tid);
-  __syncthreads();
-  const double idet = A.ihx * A.ihy[ey] * A.ihz;
-  double* xe = A.x + e * 3 * NP3;
-  // last sweep (z) straight to memory
-  constexpr int NO = NP3;
-  for (int it = tid; it < 3 * NO; it += kImThreads) {
-    const int c = it / NO, rr = it - c * NO;
-    const int o2 = rr / (NP * NP), base = rr - o2 * NP * NP;
-    const double* ip = u0 + c * NP3 + base;
-    double s = 0.0;
-#pragma unroll
-    for (int l = 0; l < NP; ++l) s += Mi[o2 * NP + l] * ip[l * NP * NP];
-    xe[it] = s * idet;
-  }
-}
-
+// The polynomial part of each enriched cell's current psi, cached for the
+// inverse mass: a = K^{-1} (N, psi)_w and 1/(r_psi, r_psi)_w.
 template <int NP, int NQ, int NQY>
-__global__ __launch_bounds__(kPrjThreads) void invmass_enriched_kernel(const InvMassArgs A) {
+__global__ __launch_bounds__(kPrjThreads) void psi_poly_kernel(const InvMassArgs A) {
   constexpr int NPT = NQ * NQY * NQ, NP3 = NP * NP * NP;
   __shared__ Tab1d<NP, NQ, NQY> T;
   __shared__ PsiPoly<NP, NQ, NQY> L;
-  __shared__ double rp[3 * NP3], y0[3 * NP3], y1[3 * NP3];
-  __shared__ double red[4 * (kPrjThreads / 64)];
-  __shared__ double sre[3];
+  __shared__ double red[kPrjThreads / 64];
   const int tid = threadIdx.x;
   const int64_t enr = blockIdx.x;
-  const int64_t e = enriched_cell_index(A.nx, A.ny, A.lower_slot, A.nslots, enr);
-  const int ey = (int)((e / A.nx) % A.ny);
   load_tab1d<NP, NQ, NQY>(A.tab, A.minv, T, tid);
-  const double* re = A.r + e * 3 * NP3;
-  for (int i = tid; i < 3 * NP3; i += kPrjThreads) rp[i] = re[i];
-  const int64_t eo = A.ncell * 3 * NP3 + enr * 3;
-  if (tid < 3) sre[tid] = A.r[eo + tid];
   __syncthreads();
   const double* psi[1] = {A.psi + enr * A.psi_pts * 4};
   psi_poly_part<1, NP, NQ, NQY>(psi, T, L, tid);
-  // K^{-1} r_bar, three components
-  sweepn<3, 0, NP, NP, NP, NP, false>(rp, y0, T.Mi, tid);
-  __syncthreads();
-  sweepn<3, 1, NP, NP, NP, NP, false>(y0, y1, T.Miy, tid);
-  __syncthreads();
-  sweepn<3, 2, NP, NP, NP, NP, false>(y1, y0, T.Mi, tid);
-  // (r_psi, r_psi)_w and a . r_bar_c
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  double v[1] = {0.0};
   for (int q = tid; q < NPT; q += kPrjThreads) {
     const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
-    const double w = T.W[qx] * T.Wy[qy] * T.W[qz];
-    v[0] += w * L.r[q] * L.r[q];
+    v[0] += T.W[qx] * T.Wy[qy] * T.W[qz] * L.r[q] * L.r[q];
   }
-  for (int B = tid; B < NP3; B += kPrjThreads) {
-    const double ab = L.b[B];
-    v[1] += ab * rp[B];
-    v[2] += ab * rp[NP3 + B];
-    v[3] += ab * rp[2 * NP3 + B];
+  block_sum<1>(v, red, tid);
+  double* out = A.apoly + enr * (NP3 + 1);
+  for (int B = tid; B < NP3; B += kPrjThreads) out[B] = L.b[B];
+  if (tid == 0) out[NP3] = (A.act[enr] && v[0] > 0.0) ? 1.0 / v[0] : 0.0;
+}
+
+constexpr int kImThreads = 64;
+
+// x = M^{-1} r, one wavefront per cell.  ENR = false: regular cells, block
+// b = ex + nx (ly + nlayers ez) with ey = layer_lo + ly; ENR = true: block b
+// = enriched index.  The cell sits in LDS once and each 1-D sweep runs in
+// place, one line per lane (a lane reads its whole line into registers
+// before writing it back), with the inverse 1-D mass matrix in registers.
+// Enriched cells use the wall-normal rule's matrix along y and the cached
+// polynomial part of psi:
+//   x~_c = (r~_c - a . r_bar_c) / (|det J| (r_psi, r_psi)),
+//   x_bar_c = |det J|^{-1} K^{-1} r_bar_c - a x~_c.
+template <int NP, bool ENR>
+__global__ __launch_bounds__(kImThreads) void invmass_kernel(const InvMassArgs A, int layer_lo, int nlayers) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
+  __shared__ double u[3 * NP3];
+  __shared__ double sa[ENR ? NP3 : 1];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  int64_t e;
+  int ey;
+  if (ENR) {
+    e = enriched_cell_index(A.nx, A.ny, A.lower_slot, A.nslots, b);
+    ey = (int)((e / A.nx) % A.ny);
+  } else {
+    const int ex = (int)(b % A.nx);
+    const int64_t t0 = b / A.nx;
+    ey = layer_lo + (int)(t0 % nlayers);
+    e = ex + (int64_t)A.nx * (ey + (int64_t)A.ny * (t0 / nlayers));
   }
-  block_sum<4>(v, red, tid);   // (its barriers also order the last sweep before the reads below)
-  const double idet = A.ihx * A.ihy[ey] * A.ihz;
-  const bool on = A.act[enr] && v[0] > 0.0;
-  const double is = on ? idet / v[0] : 0.0;
-  double xt[3];
+  const double* re = A.r + e * 3 * NP3;
+  for (int i = tid; i < 3 * NP3; i += kImThreads) u[i] = re[i];
+  double m[NP2];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) xt[c] = (sre[c] - v[1 + c]) * is;
-  double* xe = A.x + e * 3 * NP3;
-  for (int it = tid; it < 3 * NP3; it += kPrjThreads) {
-    const int c = it / NP3, B = it - c * NP3;
-    xe[it] = y0[it] * idet - L.b[B] * xt[c];
+  for (int i = 0; i < NP2; ++i) m[i] = A.minv[i];
+  const double idet = A.ihx * A.ihy[ey] * A.ihz;
+  double xt0 = 0.0, xt1 = 0.0, xt2 = 0.0;
+  if (ENR) {
+    const double* ap = A.apoly + b * (NP3 + 1);
+    for (int i = tid; i < NP3; i += kImThreads) sa[i] = ap[i];
+    __syncthreads();
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int B = tid; B < NP3; B += kImThreads) {
+      const double ab = sa[B];
+      d0 += ab * u[B];
+      d1 += ab * u[NP3 + B];
+      d2 += ab * u[2 * NP3 + B];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      d0 += __shfl_xor(d0, off, 64);
+      d1 += __shfl_xor(d1, off, 64);
+      d2 += __shfl_xor(d2, off, 64);
+    }
+    const double is = ap[NP3] * idet;
+    const int64_t eo = A.ncell * 3 * NP3 + b * 3;
+    xt0 = (A.r[eo + 0] - d0) * is;
+    xt1 = (A.r[eo + 1] - d1) * is;
+    xt2 = (A.r[eo + 2] - d2) * is;
+    __syncthreads();  // every lane has read u and r~ before anything is overwritten
+    if (tid == 0) {
+      A.x[eo + 0] = xt0;
+      A.x[eo + 1] = xt1;
+      A.x[eo + 2] = xt2;
+    }
+  } else {
+    __syncthreads();
   }
-  if (tid < 3) A.x[eo + tid] = xt[tid];
+  // lines along x (c, j, k): base c NP3 + NP (j + NP k), stride 1
+  for (int L = tid; L < 3 * NP2; L += kImThreads) {
+    double* p = u + (L / NP2) * NP3 + (L % NP2) * NP;
+    double x[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) x[l] = p[l];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) s += m[o * NP + l] * x[l];
+      p[o] = s;
+    }
+  }
+  __syncthreads();
+  if (ENR) {
+#pragma unroll
+    for (int i = 0; i < NP2; ++i) m[i] = A.minv[NP2 + i];
+  }
+  // lines along y (c, i, k): base c NP3 + i + NP2 k, stride NP
+  for (int L = tid; L < 3 * NP2; L += kImThreads) {
+    const int ik = L % NP2;
+    double* p = u + (L / NP2) * NP3 + (ik % NP) + NP2 * (ik / NP);
+    double x[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) x[l] = p[l * NP];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) s += m[o * NP + l] * x[l];
+      p[o * NP] = s;
+    }
+  }
+  __syncthreads();
+  if (ENR) {
+#pragma unroll
+    for (int i = 0; i < NP2; ++i) m[i] = A.minv[i];
+  }
+  // lines along z (c, i, j): base c NP3 + i + NP j, stride NP2, straight to memory
+  double* xe = A.x + e * 3 * NP3;
+  for (int L = tid; L < 3 * NP2; L += kImThreads) {
+    const int c = L / NP2, b0 = L % NP2;
+    const double* p = u + c * NP3 + b0;
+    const double xc = c == 0 ? xt0 : (c == 1 ? xt1 : xt2);
+    double x[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) x[l] = p[l * NP2];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) s += m[o * NP + l] * x[l];
+      s *= idet;
+      if (ENR) s -= sa[b0 + o * NP2] * xc;
+      xe[c * NP3 + b0 + o * NP2] = s;
+    }
+  }
 }
 
 }  // namespace
@@ -373,12 +433,9 @@ int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_
   A.ny = m->P.ny;
   A.nz = m->P.nz;
   A.lower_slot = m->lower_slot;
+  A.upper_slot = m->upper_slot;
   A.nslots = m->n_enr_layers;
   A.psi_pts = m->psi_pts;
-  // regular layers: all but the enriched wall-adjacent ones
-  A.layer_lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
-  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
-  A.nlayers = hi - A.layer_lo + 1;
   A.ncell = m->ncell;
   A.ihx = 1.0 / m->hx;
   A.ihz = 1.0 / m->hz;
@@ -387,29 +444,42 @@ int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_
   A.minv = m->minv;
   A.psi = m->psi;
   A.act = m->act;
+  A.apoly = m->apoly;
   A.r = r;
   A.x = x;
-  const int64_t nreg = A.nlayers > 0 ? (int64_t)m->P.nx * A.nlayers * m->P.nz : 0;
-  bool done = nreg == 0;
-#define X(p)                                                                                               \
-  if (!done && m->np_u == p) {                                                                             \
-    hipLaunchKernelGGL((invmass_regular_kernel<p>), dim3((unsigned)nreg), dim3(kImThreads), 0, s, A);       \
-    const int rc = check_hip(hipGetLastError(), "inverse mass kernel launch");                             \
-    if (rc) return rc;                                                                                     \
-    done = true;                                                                                           \
+  if (m->nenr > 0 && !m->apoly_ok) {
+    bool launched = false;
+#define X(p, q, w)                                                                                        \
+    if (!launched && m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                 \
+      hipLaunchKernelGGL((psi_poly_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
+      const int rc = check_hip(hipGetLastError(), "psi polynomial part kernel launch");                   \
+      if (rc) return rc;                                                                                  \
+      launched = true;                                                                                    \
+    }
+    DG_PRJ_COMBOS(X)
+#undef X
+    if (!launched) return set_error(DG_ERR_UNSUPPORTED, "inverse mass: (k_u+1, nq_u, nq_wn) combination not compiled");
+    m->apoly_ok = 1;
+  }
+  // regular layers: all but the enriched wall-adjacent ones
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
+#define X(p)                                                                                                 \
+  if (m->np_u == p) {                                                                                        \
+    if (nreg > 0) {                                                                                          \
+      hipLaunchKernelGGL((invmass_kernel<p, false>), dim3((unsigned)nreg), dim3(kImThreads), 0, s, A, lo, nl); \
+      const int rc = check_hip(hipGetLastError(), "inverse mass kernel launch");                             \
+      if (rc) return rc;                                                                                     \
+    }                                                                                                        \
+    if (m->nenr > 0)                                                                                         \
+      hipLaunchKernelGGL((invmass_kernel<p, true>), dim3((unsigned)m->nenr), dim3(kImThreads), 0, s, A, 0, 0); \
+    return check_hip(hipGetLastError(), "inverse mass kernel launch");                                       \
   }
   X(3) X(4) X(5) X(6)
 #undef X
-  if (!done) return set_error(DG_ERR_UNSUPPORTED, "inverse mass: degree not compiled");
-  if (m->nenr == 0) return DG_OK;
-#define X(p, q, w)                                                                                          \
-  if (m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                                  \
-    hipLaunchKernelGGL((invmass_enriched_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
-    return check_hip(hipGetLastError(), "inverse mass kernel launch");                                      \
-  }
-  DG_PRJ_COMBOS(X)
-#undef X
-  return set_error(DG_ERR_UNSUPPORTED, "inverse mass: (k_u+1, nq_u, nq_wn) combination not compiled");
+  return set_error(DG_ERR_UNSUPPORTED, "inverse mass: degree not compiled");
 }
 
 }  // namespace dgwm

@@ -79,9 +79,13 @@ def test_inverse_mass_in_place_and_after_nodal_update():
     inp = draw_inputs(Workload("im", cfg, 22, 0.5, 1.5))
     tn = np.random.default_rng(23).uniform(0.4, 1.6, (2, cfg.nz, cfg.nx))
     mesh = Mesh(cfg, inp["tau"])
-    mesh.update_wall_shear_nodes(torch.tensor(tn, device="cuda"))
     r = torch.tensor(inp["u"], device="cuda")
-    x = mesh.apply_inverse_mass(r)
+    x0 = mesh.apply_inverse_mass(r).cpu().numpy()      # fills the cache of the setup psi
+    ref0, conds0 = OP.inverse_mass(cfg, inp["u"], O.psi_volume(cfg, O.enriched_cells(cfg), tau=inp["tau"]),
+                                   return_cond=True)
+    _check(cfg, x0, ref0, conds0, range(cfg.ncell))
+    mesh.update_wall_shear_nodes(torch.tensor(tn, device="cuda"))
+    x = mesh.apply_inverse_mass(r)                      # the update invalidates the cache
     y = r.clone()
     mesh.apply_inverse_mass(y, y)
     torch.cuda.synchronize()
