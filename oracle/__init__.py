@@ -70,6 +70,8 @@ def lib():
         L.orc_psi_point_nodal.argtypes = [P, _D, ctypes.c_int64, _D, _D]
         L.orc_wall_shear_nodes.argtypes = [P, _D, _D, _D, _D]
         L.orc_psi_volume.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D]
+        L.orc_pressure_gradient.argtypes = [P, _D, _D, _D, _I64, ctypes.c_int64, _D]
+        L.orc_velocity_divergence.argtypes = [P, _D, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_enrichment_active.argtypes = [P, _D, _D, ctypes.POINTER(ctypes.c_int32)]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
         L.orc_num_threads.argtypes = []
@@ -262,6 +264,45 @@ def psi_volume(cfg, cells, tau=None, tau_nodes=None):
                               _ptr(out))
     if rc:
         raise RuntimeError(f"orc_psi_volume failed: {rc}")
+    return out
+
+
+def pressure_gradient(cfg, p, tau=None, tau_nodes=None, cells=None):
+    """Pressure gradient term (Sec. 4.2) g(v) = -(div v, p)_e + (v . n, {{p}})
+    for every velocity test function (velocity layout); psi from the per-point
+    tau or the nodal tau_nodes."""
+    pr = params(cfg)
+    p = _f64(p)
+    if p.size != num_dofs(cfg, 1):
+        raise ValueError("p has the wrong size")
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    cells = _cells(cfg, cells)
+    out = np.zeros(num_dofs(cfg, 0))
+    rc = lib().orc_pressure_gradient(ctypes.byref(pr), _ptr(p), _ptr(t) if t is not None else None,
+                                     _ptr(tn) if tn is not None else None, cells.ctypes.data_as(_I64), cells.size,
+                                     _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_pressure_gradient failed: {rc}")
+    return out
+
+
+def velocity_divergence(cfg, u, tau=None, tau_nodes=None, cells=None):
+    """Velocity divergence term (Sec. 4.2) c(q) = -(grad q, u)_e + (q, {{u}} . n)
+    for every pressure test function (pressure layout)."""
+    pr = params(cfg)
+    u = _f64(u)
+    if u.size != num_dofs(cfg, 0):
+        raise ValueError("u has the wrong size")
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    cells = _cells(cfg, cells)
+    out = np.zeros(num_dofs(cfg, 1))
+    rc = lib().orc_velocity_divergence(ctypes.byref(pr), _ptr(u), _ptr(t) if t is not None else None,
+                                       _ptr(tn) if tn is not None else None, cells.ctypes.data_as(_I64), cells.size,
+                                       _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_velocity_divergence failed: {rc}")
     return out
 
 

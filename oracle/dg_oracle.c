@@ -813,6 +813,210 @@ int orc_velocity_residual_nodal(const orc_params *P, const double *u, const doub
 }
 
 /* ------------------------------------------------------------------------ */
+/* Pressure gradient and velocity divergence terms (Sec. 4.2)                */
+/* ------------------------------------------------------------------------ */
+
+/* Face rule of face (d, s) of cell e: the tangential rules with the larger
+ * point count of the two adjacent cells (as in the velocity residual). */
+static void face_rule(const ctx *C, int64_t e, int64_t nb, int t1, int t2, const double **q1, const double **w1,
+                      int *n1, const double **q2, const double **w2, int *n2) {
+  *n1 = vel_nq(C, e, t1);
+  *n2 = vel_nq(C, e, t2);
+  *q1 = vel_q(C, e, t1, w1);
+  *q2 = vel_q(C, e, t2, w2);
+  if (nb >= 0) {
+    if (vel_nq(C, nb, t1) > *n1) { *n1 = vel_nq(C, nb, t1); *q1 = vel_q(C, nb, t1, w1); }
+    if (vel_nq(C, nb, t2) > *n2) { *n2 = vel_nq(C, nb, t2); *q2 = vel_q(C, nb, t2, w2); }
+  }
+}
+
+/* pressure p_h = sum_B N^p_B p_B at xi of cell e */
+static double eval_p(const ctx *C, const double *p, int64_t e, const double xi[3], const double Ji[3][3],
+                     double *bv, double (*bg)[3]) {
+  int n = C->npp, np3 = n * n * n;
+  basis3(n, C->glp, xi, Ji, bv, bg);
+  const double *pe = p + (int64_t)e * np3;
+  double s = 0;
+  for (int B = 0; B < np3; ++B) s += bv[B] * pe[B];
+  return s;
+}
+
+/* Pressure gradient term for every velocity test function v of cell e
+ * (N_B e_c and, in an enriched cell, psi e_c):
+ *   g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e},  {{p}} = (p- + p+)/2,
+ * with the external value p+ = p- on no-slip walls (the pressure's
+ * homogeneous Neumann condition) and the velocity quadrature of the cell and
+ * of its faces.  Out: velocity layout. */
+static void grad_cell(const ctx *C, const double *p, int64_t e, double *g, double *bv, double (*bg)[3],
+                      double *pv, double (*pg)[3]) {
+  int n = C->npu, np3 = n * n * n;
+  double *ge = g + (int64_t)e * 3 * np3;
+  double gt[3] = {0, 0, 0};
+  for (int i = 0; i < 3 * np3; ++i) ge[i] = 0.0;
+  int enriched = C->enr[e] >= 0;
+  const double *q[3], *w[3];
+  int nq[3];
+  for (int a = 0; a < 3; ++a) { q[a] = vel_q(C, e, a, &w[a]); nq[a] = vel_nq(C, e, a); }
+  for (int c3 = 0; c3 < nq[2]; ++c3)
+    for (int b = 0; b < nq[1]; ++b)
+      for (int a = 0; a < nq[0]; ++a) {
+        double xi[3] = {q[0][a], q[1][b], q[2][c3]}, X[3], J[3][3], Ji[3][3];
+        cell_map(C, e, xi, X, J);
+        double wq = fabs(inv3(J, Ji)) * w[0][a] * w[1][b] * w[2][c3];
+        double ph = eval_p(C, p, e, xi, Ji, pv, pg);
+        basis3(n, C->glu, xi, Ji, bv, bg);
+        /* div (N_B e_c) = d_c N_B */
+        for (int c = 0; c < 3; ++c)
+          for (int B = 0; B < np3; ++B) ge[c * np3 + B] -= wq * bg[B][c] * ph;
+        if (enriched) {
+          psi_pt ps;
+          eval_psi(C, e, xi, Ji, &ps);
+          for (int c = 0; c < 3; ++c) gt[c] -= wq * ps.g[c] * ph;
+        }
+      }
+  for (int f = 0; f < 6; ++f) {
+    int d = f / 2, s = f % 2;
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    int64_t nb = face_neighbor(C, e, d, s);
+    const double *q1, *w1, *q2, *w2;
+    int n1, n2;
+    face_rule(C, e, nb, t1, t2, &q1, &w1, &n1, &q2, &w2, &n2);
+    for (int b = 0; b < n2; ++b)
+      for (int a = 0; a < n1; ++a) {
+        double xi[3], X[3], J[3][3], Ji[3][3];
+        xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
+        cell_map(C, e, xi, X, J);
+        double det = fabs(inv3(J, Ji));
+        double sg = s ? 1.0 : -1.0;
+        double nv[3] = {sg * Ji[d][0], sg * Ji[d][1], sg * Ji[d][2]};
+        double nr = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        for (int k = 0; k < 3; ++k) nv[k] /= nr;
+        double wf = det * nr * w1[a] * w2[b];
+        double pm = eval_p(C, p, e, xi, Ji, pv, pg), pp = pm;
+        if (nb >= 0) {
+          double xn[3], Xn[3], Jn[3][3], Jin[3][3];
+          xn[d] = 1 - s; xn[t1] = xi[t1]; xn[t2] = xi[t2];
+          cell_map(C, nb, xn, Xn, Jn);
+          inv3(Jn, Jin);
+          pp = eval_p(C, p, nb, xn, Jin, pv, pg);
+        }
+        double pavg = 0.5 * (pm + pp);
+        basis3(n, C->glu, xi, Ji, bv, bg);
+        for (int c = 0; c < 3; ++c)
+          for (int B = 0; B < np3; ++B) ge[c * np3 + B] += wf * bv[B] * nv[c] * pavg;
+        if (enriched) {
+          psi_pt ps;
+          eval_psi(C, e, xi, Ji, &ps);
+          for (int c = 0; c < 3; ++c) gt[c] += wf * ps.psi * nv[c] * pavg;
+        }
+      }
+  }
+  if (enriched) {
+    double *go = g + C->ncell * 3 * np3 + C->enr[e] * 3;
+    for (int c = 0; c < 3; ++c) go[c] = gt[c];
+  }
+}
+
+/* Velocity divergence term for every pressure test function q of cell e:
+ *   c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e},  {{u}} = (u- + u+)/2,
+ * u the full (enriched) velocity, with the external value u+ = -u- on no-slip
+ * walls (so {{u}} = 0 there) and the velocity quadrature of the cell and of
+ * its faces.  Out: pressure layout. */
+static void div_cell(const ctx *C, const double *u, int64_t e, double *out, double *bv, double (*bg)[3],
+                     double *bv2, double (*bg2)[3], double *pv, double (*pg)[3]) {
+  int np = C->npp, np3p = np * np * np;
+  double *oe = out + (int64_t)e * np3p;
+  for (int i = 0; i < np3p; ++i) oe[i] = 0.0;
+  const double *q[3], *w[3];
+  int nq[3];
+  for (int a = 0; a < 3; ++a) { q[a] = vel_q(C, e, a, &w[a]); nq[a] = vel_nq(C, e, a); }
+  for (int c3 = 0; c3 < nq[2]; ++c3)
+    for (int b = 0; b < nq[1]; ++b)
+      for (int a = 0; a < nq[0]; ++a) {
+        double xi[3] = {q[0][a], q[1][b], q[2][c3]}, X[3], J[3][3], Ji[3][3];
+        cell_map(C, e, xi, X, J);
+        double wq = fabs(inv3(J, Ji)) * w[0][a] * w[1][b] * w[2][c3];
+        vel_pt vp;
+        eval_vel(C, u, e, xi, Ji, 0, &vp, bv, bg);
+        basis3(np, C->glp, xi, Ji, pv, pg);
+        for (int B = 0; B < np3p; ++B)
+          oe[B] -= wq * (pg[B][0] * vp.u[0] + pg[B][1] * vp.u[1] + pg[B][2] * vp.u[2]);
+      }
+  for (int f = 0; f < 6; ++f) {
+    int d = f / 2, s = f % 2;
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    int64_t nb = face_neighbor(C, e, d, s);
+    if (nb < 0) continue; /* {{u}} = 0 on a no-slip wall */
+    const double *q1, *w1, *q2, *w2;
+    int n1, n2;
+    face_rule(C, e, nb, t1, t2, &q1, &w1, &n1, &q2, &w2, &n2);
+    for (int b = 0; b < n2; ++b)
+      for (int a = 0; a < n1; ++a) {
+        double xi[3], xn[3], X[3], J[3][3], Ji[3][3], Xn[3], Jn[3][3], Jin[3][3];
+        xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
+        cell_map(C, e, xi, X, J);
+        double det = fabs(inv3(J, Ji));
+        double sg = s ? 1.0 : -1.0;
+        double nv[3] = {sg * Ji[d][0], sg * Ji[d][1], sg * Ji[d][2]};
+        double nr = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        for (int k = 0; k < 3; ++k) nv[k] /= nr;
+        double wf = det * nr * w1[a] * w2[b];
+        vel_pt pm, pp;
+        eval_vel(C, u, e, xi, Ji, 0, &pm, bv, bg);
+        xn[d] = 1 - s; xn[t1] = xi[t1]; xn[t2] = xi[t2];
+        cell_map(C, nb, xn, Xn, Jn);
+        inv3(Jn, Jin);
+        eval_vel(C, u, nb, xn, Jin, 0, &pp, bv2, bg2);
+        double un = 0;
+        for (int k = 0; k < 3; ++k) un += 0.5 * (pm.u[k] + pp.u[k]) * nv[k];
+        basis3(np, C->glp, xi, Ji, pv, pg);
+        for (int B = 0; B < np3p; ++B) oe[B] += wf * pv[B] * un;
+      }
+  }
+}
+
+static int mixed_op(const orc_params *P, const double *in, const double *tau_w, const double *tau_nodes,
+                    const int64_t *cells, int64_t ncells, double *out, int divergence) {
+  ctx C;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  ctx_activity(&C, -1);
+  int n = C.npu, np3 = n * n * n, npp3 = C.npp * C.npp * C.npp;
+  int err = 0;
+#pragma omp parallel
+  {
+    double *bv = (double *)malloc(sizeof(double) * (2 * np3 + npp3));
+    double(*bg)[3] = (double(*)[3])malloc(sizeof(double) * 3 * (2 * np3 + npp3));
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < ncells; ++i) {
+      int64_t e = cells[i];
+      if (e < 0 || e >= C.ncell) { err = -3; continue; }
+      if (divergence)
+        div_cell(&C, in, e, out, bv, bg, bv + np3, bg + np3, bv + 2 * np3, bg + 2 * np3);
+      else
+        grad_cell(&C, in, e, out, bv, bg, bv + 2 * np3, bg + 2 * np3);
+    }
+    free(bv);
+    free(bg);
+  }
+  ctx_free(&C);
+  return err;
+}
+
+/* Pressure gradient term g = P p (velocity layout) of the listed cells. */
+int orc_pressure_gradient(const orc_params *P, const double *p, const double *tau_w, const double *tau_nodes,
+                          const int64_t *cells, int64_t ncells, double *g) {
+  return mixed_op(P, p, tau_w, tau_nodes, cells, ncells, g, 0);
+}
+
+/* Velocity divergence term c = C u (pressure layout) of the listed cells. */
+int orc_velocity_divergence(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
+                            const int64_t *cells, int64_t ncells, double *c) {
+  return mixed_op(P, u, tau_w, tau_nodes, cells, ncells, c, 1);
+}
+
+/* ------------------------------------------------------------------------ */
 /* SIP Poisson operator                                                      */
 /* ------------------------------------------------------------------------ */
 
