@@ -241,6 +241,29 @@ int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, 
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall), DG_ERR_HIP. */
 int dg_apply_inverse_mass(const dg_mesh* mesh, const double* r, double* x, void* stream);
 
+/* Pressure gradient term of the dual-splitting scheme (paper Sec. 4.2):
+ *   g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}
+ * for every velocity test function v (N_B e_c, and psi e_c in enriched
+ * cells), {{p}} the central average of the two traces, on no-slip walls the
+ * external value p+ = p-.  Velocity quadrature of the cell (nq_u^3, nq_u x
+ * nq_wn x nq_u in enriched cells) and of its faces.  Flat meshes only.
+ *   p: device, dg_num_dofs(mesh, 1) doubles; g: device, dg_num_dofs(mesh, 0)
+ *   doubles (velocity layout, enrichment rows included), distinct from p.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall or a degree
+ *   combination not compiled), DG_ERR_HIP. */
+int dg_apply_pressure_gradient(const dg_mesh* mesh, const double* p, double* g, void* stream);
+
+/* Velocity divergence term (paper Sec. 4.2):
+ *   c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}
+ * for every pressure test function q, u the full velocity (psi u~ included),
+ * on no-slip walls the external value u+ = -u- (so {{u}} = 0 there); the
+ * same quadrature as the gradient, so that c = -P^T u wherever the rules
+ * integrate div(q u) exactly.  Flat meshes only.
+ *   u: device, dg_num_dofs(mesh, 0) doubles; c: device, dg_num_dofs(mesh, 1)
+ *   doubles (pressure layout), distinct from u.
+ *   Errors: as for dg_apply_pressure_gradient. */
+int dg_apply_velocity_divergence(const dg_mesh* mesh, const double* u, double* c, void* stream);
+
 /* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
  * term, flux eq. ipflux) with homogeneous Neumann data on the walls:
  *   (A p)(q) = sum_e (grad q, grad p)_e + sum_{interior F} [ -1/2 (grad q.n)(p- - p+)

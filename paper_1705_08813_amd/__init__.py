@@ -156,6 +156,26 @@ class Mesh:
         _lib.check(_lib.lib().dg_apply_inverse_mass(self.handle, _dptr(r), _dptr(x), _stream_ptr(stream)))
         return x
 
+    def apply_pressure_gradient(self, p, g=None, stream=None):
+        """Pressure gradient term P p (velocity layout, Sec. 4.2)."""
+        import torch
+        self._check_f64(p, self.n_p, "p")
+        if g is None:
+            g = torch.empty(self.n_vel, dtype=torch.float64, device=self.device)
+        self._check_f64(g, self.n_vel, "g")
+        _lib.check(_lib.lib().dg_apply_pressure_gradient(self.handle, _dptr(p), _dptr(g), _stream_ptr(stream)))
+        return g
+
+    def apply_velocity_divergence(self, u, c=None, stream=None):
+        """Velocity divergence term C u (pressure layout, Sec. 4.2)."""
+        import torch
+        self._check_f64(u, self.n_vel, "u")
+        if c is None:
+            c = torch.empty(self.n_p, dtype=torch.float64, device=self.device)
+        self._check_f64(c, self.n_p, "c")
+        _lib.check(_lib.lib().dg_apply_velocity_divergence(self.handle, _dptr(u), _dptr(c), _stream_ptr(stream)))
+        return c
+
     def enrichment_active(self, stream=None):
         """Activity flags (int32 device tensor, 1 on / 0 switched off) of the
         enriched cells in the current space."""

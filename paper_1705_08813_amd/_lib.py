@@ -61,6 +61,8 @@ _SIGS = {
     "dg_update_wall_shear_nodes": (ctypes.c_int, [_VP, _VP, _VP]),
     "dg_project_velocity": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "dg_apply_inverse_mass": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "dg_apply_pressure_gradient": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "dg_apply_velocity_divergence": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "dg_enrichment_active": (ctypes.c_int, [_VP, _VP, _VP]),
     "dg_num_dofs": (ctypes.c_int64, [_VP, ctypes.c_int]),
     "dg_num_enriched": (ctypes.c_int64, [_VP]),

@@ -144,6 +144,7 @@ struct dg_mesh {
   double* eta;            // ny+1 wall-normal vertex coordinates
   double* tab_u;          // velocity tables (np_u, nq_u, nq_wn)
   double* tab_p;          // pressure tables (np_p, nq_p, nq_p)
+  double* tab_pu;         // pressure basis at the velocity rules (np_p, nq_u, nq_wn)
   double* tau;            // wall shear stress copy, per wall-face Gauss point
   double* tau_nodes;      // nodal wall shear stress copy [wall][nz][nx] (flat walls)
   int tau_nodal = 0;      // 1: psi was computed from tau_nodes, 0: from tau
@@ -216,6 +217,8 @@ size_t solve_bytes_mesh(const dg_mesh& m);
 // device data of the hierarchy (levels' heights and diagonals, coarse inverse)
 int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+// out = C u (divergence, pressure layout) or P p (gradient, velocity layout), flat meshes
+int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s);
 // x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)
 int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s);
 // u_new = L2 projection of u_old from the space of psi_prev onto that of psi
