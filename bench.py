@@ -331,6 +331,31 @@ def main():
                                   "hbm_frac": im_bytes / (t_im * 1e-3) / 8e12}
         del pm, un, uw, tnd, xm
     if not args.no_extras:
+        # pressure gradient and velocity divergence terms (Sec. 4.2) on the same mesh and data
+        print("bench: pressure gradient and velocity divergence", file=sys.stderr, flush=True)
+        gv = torch.empty_like(u)
+        cp = torch.empty_like(p)
+        for _ in range(3):
+            mesh.apply_pressure_gradient(p, gv)
+            mesh.apply_velocity_divergence(u, cp)
+        ev6 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        nrep = max(10, K)
+        ev6[0].record(stream)
+        for _ in range(nrep):
+            mesh.apply_pressure_gradient(p, gv)
+        ev6[1].record(stream)
+        for _ in range(nrep):
+            mesh.apply_velocity_divergence(u, cp)
+        ev6[2].record(stream)
+        torch.cuda.synchronize()
+        t_g = ev6[0].elapsed_time(ev6[1]) / nrep
+        t_c = ev6[1].elapsed_time(ev6[2]) / nrep
+        # algorithmic bytes: one input and one output vector each
+        b_gc = 8.0 * (n_vel + n_p)
+        extras["pressure_gradient"] = {"ms": t_g, "GBps_alg": b_gc / (t_g * 1e-3) / 1e9}
+        extras["velocity_divergence"] = {"ms": t_c, "GBps_alg": b_gc / (t_c * 1e-3) / 1e9}
+        del gv, cp
+    if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)
         wc = PRESETS["curved"]

@@ -16,7 +16,7 @@ thread_local std::string g_err;
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 struct WsLayout {
-  size_t eta, hy, tab_u, tab_p, tab_pu, tau, tau_nodes, ws_part, psi, psi_prev, act, act_prev, minv, apoly, diag, diag32, geo,
+  size_t eta, hy, tab_u, tab_p, tau, tau_nodes, ws_part, psi, psi_prev, act, act_prev, minv, apoly, diag, diag32, geo,
       meas, tauF, wdist;
   size_t mg_hy[kMaxLevels], mg_diag[kMaxLevels], mg_diag32[kMaxLevels];
   size_t cinv, cinv32, cscr;  // coarsest pseudo-inverse (FP64, FP32) and its assembly scratch
@@ -147,7 +147,6 @@ WsLayout layout(const dg_mesh& m) {
   o = up256(o + sizeof(double) * (tab_layout(m.np_u, m.P.nq_u, m.P.nq_wn).size + m.P.nq_u + m.P.nq_wn));
   L.tab_p = o;
   o = up256(o + sizeof(double) * (tab_layout(m.np_p, m.P.nq_p, m.P.nq_p).size + poi_ops(m.np_p).size));
-  L.tab_pu = o; o = up256(o + sizeof(double) * tab_layout(m.np_p, m.P.nq_u, m.P.nq_wn).size);
   L.tau = o; o = up256(o + sizeof(double) * m.n_tau);
   const size_t nwall = m.curved || m.P.fully_periodic ? 0 : 2 * (size_t)m.P.nz * m.P.nx;
   L.tau_nodes = o; o = up256(o + sizeof(double) * nwall);
@@ -239,7 +238,6 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   m->hy = reinterpret_cast<double*>(base + W.hy);
   m->tab_u = reinterpret_cast<double*>(base + W.tab_u);
   m->tab_p = reinterpret_cast<double*>(base + W.tab_p);
-  m->tab_pu = reinterpret_cast<double*>(base + W.tab_pu);
   m->tau = reinterpret_cast<double*>(base + W.tau);
   m->tau_nodes = reinterpret_cast<double*>(base + W.tau_nodes);
   m->ws_part = reinterpret_cast<double*>(base + W.ws_part);
@@ -286,8 +284,6 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   for (int q = 0; q < P.nq_wn; ++q) tu[Lu.size + P.nq_u + q] = tu[Lu.gy + q];
   fill_tables(m->np_p, P.nq_p, P.nq_p, tp.data());
   fill_poisson_ops(m->np_p, P.nq_p, tp.data() + tab_layout(m->np_p, P.nq_p, P.nq_p).size);
-  std::vector<double> tpu(tab_layout(m->np_p, P.nq_u, P.nq_wn).size);
-  fill_tables(m->np_p, P.nq_u, P.nq_wn, tpu.data());
   std::vector<double> tau(m->n_tau, 1.0);
   if (tau_w_host) {
     for (int64_t i = 0; i < m->n_tau; ++i) {
@@ -302,7 +298,6 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   if (!rc) rc = check_hip(hipMemcpyAsync(m->hy, hy.data(), sizeof(double) * hy.size(), hipMemcpyHostToDevice, s), "copy");
   if (!rc) rc = check_hip(hipMemcpyAsync(m->tab_u, tu.data(), sizeof(double) * tu.size(), hipMemcpyHostToDevice, s), "copy");
   if (!rc) rc = check_hip(hipMemcpyAsync(m->tab_p, tp.data(), sizeof(double) * tp.size(), hipMemcpyHostToDevice, s), "copy");
-  if (!rc) rc = check_hip(hipMemcpyAsync(m->tab_pu, tpu.data(), sizeof(double) * tpu.size(), hipMemcpyHostToDevice, s), "copy");
   if (!rc) rc = check_hip(hipMemcpyAsync(m->tau, tau.data(), sizeof(double) * tau.size(), hipMemcpyHostToDevice, s), "copy");
   // curved wall: distances of the wall-adjacent vertex rows to the closest
   // wall vertex (paper Sec. 3.2: y_B is the distance to the closest wall node)

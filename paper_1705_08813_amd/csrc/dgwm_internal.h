@@ -144,7 +144,6 @@ struct dg_mesh {
   double* eta;            // ny+1 wall-normal vertex coordinates
   double* tab_u;          // velocity tables (np_u, nq_u, nq_wn)
   double* tab_p;          // pressure tables (np_p, nq_p, nq_p)
-  double* tab_pu;         // pressure basis at the velocity rules (np_p, nq_u, nq_wn)
   double* tau;            // wall shear stress copy, per wall-face Gauss point
   double* tau_nodes;      // nodal wall shear stress copy [wall][nz][nx] (flat walls)
   int tau_nodal = 0;      // 1: psi was computed from tau_nodes, 0: from tau
