@@ -71,6 +71,8 @@ def lib():
         L.orc_wall_shear_nodes.argtypes = [P, _D, _D, _D, _D]
         L.orc_psi_volume.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_pressure_gradient.argtypes = [P, _D, _D, _D, _I64, ctypes.c_int64, _D]
+        L.orc_divdiv_tau.argtypes = [P, _D, _D, _D, ctypes.c_double, _I64, ctypes.c_int64, _D]
+        L.orc_divdiv_apply.argtypes = [P, _D, _D, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_velocity_divergence.argtypes = [P, _D, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_enrichment_active.argtypes = [P, _D, _D, ctypes.POINTER(ctypes.c_int32)]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
@@ -303,6 +305,45 @@ def velocity_divergence(cfg, u, tau=None, tau_nodes=None, cells=None):
                                        _ptr(out))
     if rc:
         raise RuntimeError(f"orc_velocity_divergence failed: {rc}")
+    return out
+
+
+def divdiv_tau(cfg, u, dt_over_cr, tau=None, tau_nodes=None, cells=None):
+    """tau_D per cell (Sec. 4.2, eq. tauD): volume-averaged |u| times the cube
+    root of the cell volume times dt/Cr."""
+    pr = params(cfg)
+    u = _f64(u)
+    if u.size != num_dofs(cfg, 0):
+        raise ValueError("u has the wrong size")
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    cells = _cells(cfg, cells)
+    out = np.zeros(pr.nx * pr.ny * pr.nz)
+    rc = lib().orc_divdiv_tau(ctypes.byref(pr), _ptr(u), _ptr(t) if t is not None else None,
+                              _ptr(tn) if tn is not None else None, float(dt_over_cr), cells.ctypes.data_as(_I64),
+                              cells.size, _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_divdiv_tau failed: {rc}")
+    return out
+
+
+def divdiv_apply(cfg, u, tau_d, tau=None, tau_nodes=None, cells=None):
+    """Div-div penalty (Sec. 4.2, eq. div-div) D(v, u) = (div v, tau_D div u)_e for
+    every velocity test function (velocity layout)."""
+    pr = params(cfg)
+    u = _f64(u)
+    td = _f64(tau_d)
+    if u.size != num_dofs(cfg, 0) or td.size != pr.nx * pr.ny * pr.nz:
+        raise ValueError("u or tau_d has the wrong size")
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    cells = _cells(cfg, cells)
+    out = np.zeros(num_dofs(cfg, 0))
+    rc = lib().orc_divdiv_apply(ctypes.byref(pr), _ptr(u), _ptr(t) if t is not None else None,
+                                _ptr(tn) if tn is not None else None, _ptr(td), cells.ctypes.data_as(_I64),
+                                cells.size, _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_divdiv_apply failed: {rc}")
     return out
 
 

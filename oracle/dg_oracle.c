@@ -1017,6 +1017,107 @@ int orc_velocity_divergence(const orc_params *P, const double *u, const double *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Div-div penalty (Sec. 4.2, eq. div-div)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* tau_D of each listed cell: ||u||_e h_e dt_over_cr, ||u||_e the volume
+ * average of |u| over the cell (the full velocity, with the cell's velocity
+ * rule) and h_e the cube root of the cell volume. */
+int orc_divdiv_tau(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
+                   double dt_over_cr, const int64_t *cells, int64_t ncells, double *tau_d) {
+  ctx C;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  ctx_activity(&C, -1);
+  int n = C.npu, np3 = n * n * n;
+  int err = 0;
+#pragma omp parallel
+  {
+    double *bv = (double *)malloc(sizeof(double) * np3);
+    double(*bg)[3] = (double(*)[3])malloc(sizeof(double) * 3 * np3);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < ncells; ++i) {
+      int64_t e = cells[i];
+      if (e < 0 || e >= C.ncell) { err = -3; continue; }
+      const double *q[3], *w[3];
+      int nq[3];
+      for (int a = 0; a < 3; ++a) { q[a] = vel_q(&C, e, a, &w[a]); nq[a] = vel_nq(&C, e, a); }
+      double vol = 0, mag = 0;
+      for (int c3 = 0; c3 < nq[2]; ++c3)
+        for (int b = 0; b < nq[1]; ++b)
+          for (int a = 0; a < nq[0]; ++a) {
+            double xi[3] = {q[0][a], q[1][b], q[2][c3]}, X[3], J[3][3], Ji[3][3];
+            cell_map(&C, e, xi, X, J);
+            double wq = fabs(inv3(J, Ji)) * w[0][a] * w[1][b] * w[2][c3];
+            vel_pt vp;
+            eval_vel(&C, u, e, xi, Ji, 0, &vp, bv, bg);
+            vol += wq;
+            mag += wq * sqrt(vp.u[0] * vp.u[0] + vp.u[1] * vp.u[1] + vp.u[2] * vp.u[2]);
+          }
+      tau_d[e] = mag / vol * cbrt(vol) * dt_over_cr;
+    }
+    free(bv);
+    free(bg);
+  }
+  ctx_free(&C);
+  return err;
+}
+
+/* Div-div penalty D(v, u) = (div v, tau_D div u)_e for every velocity test
+ * function v of the listed cells (N_B e_c, and psi e_c in enriched cells),
+ * u the full velocity, tau_D per cell, the cell's velocity rule.  Out:
+ * velocity layout. */
+int orc_divdiv_apply(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
+                     const double *tau_d, const int64_t *cells, int64_t ncells, double *out) {
+  ctx C;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  ctx_activity(&C, -1);
+  int n = C.npu, np3 = n * n * n;
+  int err = 0;
+#pragma omp parallel
+  {
+    double *bv = (double *)malloc(sizeof(double) * np3);
+    double(*bg)[3] = (double(*)[3])malloc(sizeof(double) * 3 * np3);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < ncells; ++i) {
+      int64_t e = cells[i];
+      if (e < 0 || e >= C.ncell) { err = -3; continue; }
+      double *oe = out + e * 3 * np3, ot[3] = {0, 0, 0};
+      for (int k = 0; k < 3 * np3; ++k) oe[k] = 0.0;
+      const double *q[3], *w[3];
+      int nq[3];
+      for (int a = 0; a < 3; ++a) { q[a] = vel_q(&C, e, a, &w[a]); nq[a] = vel_nq(&C, e, a); }
+      for (int c3 = 0; c3 < nq[2]; ++c3)
+        for (int b = 0; b < nq[1]; ++b)
+          for (int a = 0; a < nq[0]; ++a) {
+            double xi[3] = {q[0][a], q[1][b], q[2][c3]}, X[3], J[3][3], Ji[3][3];
+            cell_map(&C, e, xi, X, J);
+            double wq = fabs(inv3(J, Ji)) * w[0][a] * w[1][b] * w[2][c3];
+            vel_pt vp;
+            eval_vel(&C, u, e, xi, Ji, 0, &vp, bv, bg);
+            double f = wq * tau_d[e] * (vp.g[0][0] + vp.g[1][1] + vp.g[2][2]);
+            /* div (N_B e_c) = d_c N_B;  div (psi e_c) = d_c psi */
+            for (int c = 0; c < 3; ++c)
+              for (int B = 0; B < np3; ++B) oe[c * np3 + B] += bg[B][c] * f;
+            if (vp.enriched)
+              for (int c = 0; c < 3; ++c) ot[c] += vp.psi.g[c] * f;
+          }
+      if (C.enr[e] >= 0) {
+        double *oo = out + C.ncell * 3 * np3 + C.enr[e] * 3;
+        for (int c = 0; c < 3; ++c) oo[c] = ot[c];
+      }
+    }
+    free(bv);
+    free(bg);
+  }
+  ctx_free(&C);
+  return err;
+}
+
+/* ------------------------------------------------------------------------ */
 /* SIP Poisson operator                                                      */
 /* ------------------------------------------------------------------------ */
 
