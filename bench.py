@@ -354,7 +354,24 @@ def main():
         b_gc = 8.0 * (n_vel + n_p)
         extras["pressure_gradient"] = {"ms": t_g, "GBps_alg": b_gc / (t_g * 1e-3) / 1e9}
         extras["velocity_divergence"] = {"ms": t_c, "GBps_alg": b_gc / (t_c * 1e-3) / 1e9}
-        del gv, cp
+        # div-div penalty: tau_D from the velocity, then D u (16 B per unknown plus tau_D)
+        td = mesh.divdiv_tau(u, 0.05)
+        for _ in range(3):
+            mesh.divdiv_tau(u, 0.05, td)
+            mesh.apply_divdiv(td, u, gv)
+        ev7 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev7[0].record(stream)
+        for _ in range(nrep):
+            mesh.divdiv_tau(u, 0.05, td)
+        ev7[1].record(stream)
+        for _ in range(nrep):
+            mesh.apply_divdiv(td, u, gv)
+        ev7[2].record(stream)
+        torch.cuda.synchronize()
+        t_dd = ev7[1].elapsed_time(ev7[2]) / nrep
+        extras["divdiv"] = {"tau_ms": ev7[0].elapsed_time(ev7[1]) / nrep, "apply_ms": t_dd,
+                            "apply_GBps_alg": 16.0 * n_vel / (t_dd * 1e-3) / 1e9}
+        del gv, cp, td
     if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)

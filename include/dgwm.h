@@ -264,6 +264,24 @@ int dg_apply_pressure_gradient(const dg_mesh* mesh, const double* p, double* g, 
  *   Errors: as for dg_apply_pressure_gradient. */
 int dg_apply_velocity_divergence(const dg_mesh* mesh, const double* u, double* c, void* stream);
 
+/* Div-div penalty parameter of the projection step (paper Sec. 4.2, eq.
+ * tauD), per cell: tau_D,e = ||u||_e h_e dt_over_cr with ||u||_e the volume
+ * average of |u| over the cell (u the full velocity, psi u~ included, the
+ * cell's velocity rule), h_e the cube root of the cell volume and dt_over_cr
+ * the time step over the global Courant number.
+ *   u: device, dg_num_dofs(mesh, 0) doubles (the previous step's velocity);
+ *   tau_d: device output, nx*ny*nz doubles in cell order.  Flat meshes only.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
+int dg_divdiv_tau(const dg_mesh* mesh, const double* u, double dt_over_cr, double* tau_d, void* stream);
+
+/* Div-div penalty (paper Sec. 4.2, eq. div-div): out(v) = (div v, tau_D,e div u)_e
+ * for every velocity test function v (N_B e_c, and psi e_c in enriched cells),
+ * u the full velocity, with the cell's velocity rule; cell-local.
+ *   tau_d: device, nx*ny*nz doubles (e.g. from dg_divdiv_tau); u, out:
+ *   device, dg_num_dofs(mesh, 0) doubles, distinct.  Flat meshes only.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
+int dg_apply_divdiv(const dg_mesh* mesh, const double* tau_d, const double* u, double* out, void* stream);
+
 /* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
  * term, flux eq. ipflux) with homogeneous Neumann data on the walls:
  *   (A p)(q) = sum_e (grad q, grad p)_e + sum_{interior F} [ -1/2 (grad q.n)(p- - p+)

@@ -176,6 +176,33 @@ class Mesh:
         _lib.check(_lib.lib().dg_apply_velocity_divergence(self.handle, _dptr(u), _dptr(c), _stream_ptr(stream)))
         return c
 
+    @property
+    def n_cells(self):
+        p = self.params
+        return p.nx * p.ny * p.nz
+
+    def divdiv_tau(self, u, dt_over_cr, tau_d=None, stream=None):
+        """Per-cell div-div penalty parameter tau_D (Sec. 4.2, eq. tauD)."""
+        import torch
+        self._check_f64(u, self.n_vel, "u")
+        if tau_d is None:
+            tau_d = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        self._check_f64(tau_d, self.n_cells, "tau_d")
+        _lib.check(_lib.lib().dg_divdiv_tau(self.handle, _dptr(u), float(dt_over_cr), _dptr(tau_d),
+                                            _stream_ptr(stream)))
+        return tau_d
+
+    def apply_divdiv(self, tau_d, u, out=None, stream=None):
+        """Div-div penalty D u (Sec. 4.2, eq. div-div), velocity layout."""
+        import torch
+        self._check_f64(tau_d, self.n_cells, "tau_d")
+        self._check_f64(u, self.n_vel, "u")
+        if out is None:
+            out = torch.empty_like(u)
+        self._check_f64(out, self.n_vel, "out")
+        _lib.check(_lib.lib().dg_apply_divdiv(self.handle, _dptr(tau_d), _dptr(u), _dptr(out), _stream_ptr(stream)))
+        return out
+
     def enrichment_active(self, stream=None):
         """Activity flags (int32 device tensor, 1 on / 0 switched off) of the
         enriched cells in the current space."""

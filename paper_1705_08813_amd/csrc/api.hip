@@ -426,6 +426,23 @@ int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, v
   return launch_divgrad(m, true, u, c, static_cast<hipStream_t>(stream));
 }
 
+int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* tau_d, void* stream) {
+  if (!m || !u || !tau_d) return set_error(DG_ERR_ARG, "mesh/u/tau_d is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
+  if (!(dt_over_cr >= 0) || !std::isfinite(dt_over_cr)) return set_error(DG_ERR_ARG, "dt/Cr must be >= 0 and finite");
+  if (!aligned256(u) || !aligned256(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must be 256-byte aligned");
+  return launch_divdiv(m, true, u, nullptr, dt_over_cr, tau_d, static_cast<hipStream_t>(stream));
+}
+
+int dg_apply_divdiv(const dg_mesh* m, const double* tau_d, const double* u, double* out, void* stream) {
+  if (!m || !tau_d || !u || !out) return set_error(DG_ERR_ARG, "mesh/tau_d/u/out is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
+  if (u == out) return set_error(DG_ERR_ARG, "u and out must not alias");
+  if (!aligned256(u) || !aligned256(out) || !aligned256(tau_d))
+    return set_error(DG_ERR_ARG, "tau_d, u and out must be 256-byte aligned");
+  return launch_divdiv(m, false, u, tau_d, 0.0, out, static_cast<hipStream_t>(stream));
+}
+
 int dg_enrichment_active(const dg_mesh* m, int32_t* flags, void* stream) {
   if (!m || !flags) return set_error(DG_ERR_ARG, "mesh/flags is NULL");
   if (m->nenr == 0) return DG_OK;

@@ -216,6 +216,9 @@ size_t solve_bytes_mesh(const dg_mesh& m);
 // device data of the hierarchy (levels' heights and diagonals, coarse inverse)
 int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+// div-div penalty: tau_D per cell from u (tau = true, out: ncell doubles) or out = D u with tau_d
+int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr, double* out,
+                  hipStream_t s);
 // out = C u (divergence, pressure layout) or P p (gradient, velocity layout), flat meshes
 int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s);
 // x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)

@@ -1,0 +1,235 @@
+// Div-div penalty of the projection step (arXiv 1705.08813, Sec. 4.2, eqs.
+// div-div and tauD), FP64, flat (box) meshes.
+//
+//   tau_D,e = ||u||_e h_e dt/Cr,   ||u||_e = |Omega_e|^{-1} int_e |u| dOmega,  h_e = |Omega_e|^{1/3}
+//   D(v, u) = (div v, tau_D,e div u)_e
+//
+// for every velocity test function v (N_B e_c, and psi e_c in enriched
+// cells), u the full velocity (psi u~ included), with the velocity
+// quadrature of the cell (nq^3, nq x nqy x nq in enriched cells).  Both are
+// cell-local: one workgroup per cell, sum-factorized sweeps with the 1-D
+// tables as compile-time literals (the three components' sweeps of a phase
+// run on separate wavefronts), no faces.
+#include "ctab.h"
+#include "kern_common.h"
+
+namespace dgwm {
+
+namespace {
+
+constexpr int kDdThreads = 256;
+
+struct DdArgs {
+  int nx, ny, nz, lower_slot, nslots, psi_pts;
+  int64_t ncell;
+  double hx, hz, dt_over_cr;
+  const double* hy;        // ny heights
+  const double* psi;       // [enr][psi_pts][4]
+  const double* u;
+  const double* tau_d;     // [cell] (apply)
+  double* out;             // tau_d [cell] (tau kernel) or D u (velocity layout)
+};
+
+template <int NP, int NQ>
+using MS = ct::MatS<NP, NQ>;
+template <int NP, int NQ>
+using MD = ct::MatSd<NP, NQ>;
+
+// Cell of block b: regular cells b = ex + nx (ly + nlayers ez), ey = layer_lo
+// + ly; enriched cells b = enriched index.
+template <bool ENR>
+__device__ __forceinline__ int64_t dd_cell(const DdArgs& A, int64_t b, int layer_lo, int nlayers, int& ey) {
+  const int ex = (int)(b % A.nx);
+  const int64_t t0 = b / A.nx;
+  int64_t ez;
+  if (ENR) {
+    const int slot = (int)(t0 % A.nslots);
+    ez = t0 / A.nslots;
+    ey = slot == A.lower_slot ? 0 : A.ny - 1;
+  } else {
+    ey = layer_lo + (int)(t0 % nlayers);
+    ez = t0 / nlayers;
+  }
+  return ex + (int64_t)A.nx * (ey + (int64_t)A.ny * ez);
+}
+
+// Fixed-order block sum of NV values per thread (every thread gets the sums).
+template <int NV>
+__device__ __forceinline__ void dd_block_sum(double (&v)[NV], double* red, int tid) {
+  constexpr int NW = kDdThreads / 64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += __shfl_down(v[i], off, 64);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[i * NW + (tid >> 6)] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    v[i] = 0.0;
+    for (int w = 0; w < NW; ++w) v[i] += red[i * NW + w];
+  }
+}
+
+template <int NP, int NQ, int NQY, bool ENR>
+__global__ __launch_bounds__(kDdThreads) void divdiv_tau_kernel(const DdArgs A, int layer_lo, int nlayers) {
+  constexpr int NP3 = NP * NP * NP, NPT = NQ * NQY * NQ;
+  constexpr auto& tq = ct::tab<NP, NQ>;
+  constexpr auto& ty = ct::tab<NP, NQY>;
+  __shared__ double su[3 * NP3];
+  __shared__ double w0[3 * NPT], w1[3 * NPT];
+  __shared__ double ut[3];
+  __shared__ double red[kDdThreads / 64];
+  const int tid = threadIdx.x;
+  int ey;
+  const int64_t b = blockIdx.x;
+  const int64_t e = dd_cell<ENR>(A, b, layer_lo, nlayers, ey);
+  const double* ue = A.u + e * 3 * NP3;
+  for (int i = tid; i < 3 * NP3; i += kDdThreads) su[i] = ue[i];
+  if (ENR && tid < 3) ut[tid] = A.u[A.ncell * 3 * NP3 + b * 3 + tid];
+  __syncthreads();
+  sweep_c<0, NP, NP, NP, NQ, false, false, MS<NP, NQ>>(su, NP3, w0, NPT, 1.0, 3);
+  __syncthreads();
+  sweep_c<1, NQ, NP, NP, NQY, false, false, MS<NP, NQY>>(w0, NPT, w1, NPT, 1.0, 3);
+  __syncthreads();
+  sweep_c<2, NQ, NQY, NP, NQ, false, false, MS<NP, NQ>>(w1, NPT, w0, NPT, 1.0, 3);
+  __syncthreads();
+  double v[1] = {0.0};
+  for (int q = tid; q < NPT; q += kDdThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+    double a = w0[q], bb = w0[NPT + q], c = w0[2 * NPT + q];
+    if (ENR) {
+      const double ps = A.psi[(b * A.psi_pts + q) * 4];
+      a += ps * ut[0];
+      bb += ps * ut[1];
+      c += ps * ut[2];
+    }
+    v[0] += tq.w[qx] * ty.w[qy] * tq.w[qz] * sqrt(a * a + bb * bb + c * c);
+  }
+  dd_block_sum<1>(v, red, tid);
+  if (tid == 0) {
+    // reference weights sum to 1: the volume average of |u| is v[0] itself
+    const double vol = A.hx * A.hy[ey] * A.hz;
+    A.out[e] = v[0] * cbrt(vol) * A.dt_over_cr;
+  }
+}
+
+template <int NP, int NQ, int NQY, bool ENR>
+__global__ __launch_bounds__(kDdThreads) void divdiv_apply_kernel(const DdArgs A, int layer_lo, int nlayers) {
+  constexpr int NP3 = NP * NP * NP, NPT = NQ * NQY * NQ;
+  constexpr auto& tq = ct::tab<NP, NQ>;
+  constexpr auto& ty = ct::tab<NP, NQY>;
+  __shared__ double su[3 * NP3];
+  __shared__ double w0[3 * NPT], w1[3 * NPT];
+  __shared__ double ut[3];
+  __shared__ double red[3 * (kDdThreads / 64)];
+  const int tid = threadIdx.x;
+  int ey;
+  const int64_t b = blockIdx.x;
+  const int64_t e = dd_cell<ENR>(A, b, layer_lo, nlayers, ey);
+  const double* ue = A.u + e * 3 * NP3;
+  for (int i = tid; i < 3 * NP3; i += kDdThreads) su[i] = ue[i];
+  if (ENR && tid < 3) ut[tid] = A.u[A.ncell * 3 * NP3 + b * 3 + tid];
+  __syncthreads();
+  const double h[3] = {A.hx, A.hy[ey], A.hz};
+  // d_c u_c at the points: component c takes the derivative table along c
+  sweep_c<0, NP, NP, NP, NQ, false, false, MD<NP, NQ>>(su, NP3, w0, NPT, 1.0, 1, 0);
+  sweep_c<0, NP, NP, NP, NQ, false, false, MS<NP, NQ>>(su + NP3, NP3, w0 + NPT, NPT, 1.0, 1, 64);
+  sweep_c<0, NP, NP, NP, NQ, false, false, MS<NP, NQ>>(su + 2 * NP3, NP3, w0 + 2 * NPT, NPT, 1.0, 1, 128);
+  __syncthreads();
+  sweep_c<1, NQ, NP, NP, NQY, false, false, MS<NP, NQY>>(w0, NPT, w1, NPT, 1.0, 1, 0);
+  sweep_c<1, NQ, NP, NP, NQY, false, false, MD<NP, NQY>>(w0 + NPT, NPT, w1 + NPT, NPT, 1.0, 1, 64);
+  sweep_c<1, NQ, NP, NP, NQY, false, false, MS<NP, NQY>>(w0 + 2 * NPT, NPT, w1 + 2 * NPT, NPT, 1.0, 1, 128);
+  __syncthreads();
+  sweep_c<2, NQ, NQY, NP, NQ, false, false, MS<NP, NQ>>(w1, NPT, w0, NPT, 1.0, 1, 0);
+  sweep_c<2, NQ, NQY, NP, NQ, false, false, MS<NP, NQ>>(w1 + NPT, NPT, w0 + NPT, NPT, 1.0, 1, 64);
+  sweep_c<2, NQ, NQY, NP, NQ, false, false, MD<NP, NQ>>(w1 + 2 * NPT, NPT, w0 + 2 * NPT, NPT, 1.0, 1, 128);
+  __syncthreads();
+  // f = w |J| tau_D div u; tested with d_c N_B = (1/h_c) d/dxi_c and, in enriched cells, d_c psi
+  const double scale = h[0] * h[1] * h[2] * A.tau_d[e];
+  double ve[3] = {0.0, 0.0, 0.0};
+  for (int q = tid; q < NPT; q += kDdThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+    double dv = w0[q] / h[0] + w0[NPT + q] / h[1] + w0[2 * NPT + q] / h[2];
+    const double* ps = ENR ? A.psi + (b * A.psi_pts + q) * 4 : nullptr;
+    if (ENR) dv += ps[1] * ut[0] + ps[2] * ut[1] + ps[3] * ut[2];
+    const double f = tq.w[qx] * ty.w[qy] * tq.w[qz] * scale * dv;
+    if (ENR) {
+      ve[0] += ps[1] * f;
+      ve[1] += ps[2] * f;
+      ve[2] += ps[3] * f;
+    }
+    w1[q] = f / h[0];
+    w1[NPT + q] = f / h[1];
+    w1[2 * NPT + q] = f / h[2];
+  }
+  __syncthreads();
+  sweep_c<0, NQ, NQY, NQ, NP, true, false, MD<NP, NQ>>(w1, NPT, w0, NPT, 1.0, 1, 0);
+  sweep_c<0, NQ, NQY, NQ, NP, true, false, MS<NP, NQ>>(w1 + NPT, NPT, w0 + NPT, NPT, 1.0, 1, 64);
+  sweep_c<0, NQ, NQY, NQ, NP, true, false, MS<NP, NQ>>(w1 + 2 * NPT, NPT, w0 + 2 * NPT, NPT, 1.0, 1, 128);
+  __syncthreads();
+  sweep_c<1, NP, NQY, NQ, NP, true, false, MS<NP, NQY>>(w0, NPT, w1, NPT, 1.0, 1, 0);
+  sweep_c<1, NP, NQY, NQ, NP, true, false, MD<NP, NQY>>(w0 + NPT, NPT, w1 + NPT, NPT, 1.0, 1, 64);
+  sweep_c<1, NP, NQY, NQ, NP, true, false, MS<NP, NQY>>(w0 + 2 * NPT, NPT, w1 + 2 * NPT, NPT, 1.0, 1, 128);
+  __syncthreads();
+  double* oe = A.out + e * 3 * NP3;
+  sweep_c<2, NP, NP, NQ, NP, true, false, MS<NP, NQ>>(w1, NPT, oe, NP3, 1.0, 1, 0);
+  sweep_c<2, NP, NP, NQ, NP, true, false, MS<NP, NQ>>(w1 + NPT, NPT, oe + NP3, NP3, 1.0, 1, 64);
+  sweep_c<2, NP, NP, NQ, NP, true, false, MD<NP, NQ>>(w1 + 2 * NPT, NPT, oe + 2 * NP3, NP3, 1.0, 1, 128);
+  if (ENR) {
+    dd_block_sum<3>(ve, red, tid);
+    if (tid < 3) A.out[A.ncell * 3 * NP3 + b * 3 + tid] = ve[tid];
+  }
+}
+
+}  // namespace
+
+#define DG_DD_COMBOS(X) X(3, 4, 8) X(3, 4, 4) X(4, 4, 8) X(4, 5, 8) X(4, 5, 5) X(5, 7, 8) X(6, 8, 8)
+
+int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr, double* out,
+                  hipStream_t s) {
+  DdArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  A.ncell = m->ncell;
+  A.hx = m->hx;
+  A.hz = m->hz;
+  A.dt_over_cr = dt_over_cr;
+  A.hy = m->hy;
+  A.psi = m->psi;
+  A.u = u;
+  A.tau_d = tau_d;
+  A.out = out;
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
+  const int nqw = m->nenr > 0 ? m->P.nq_wn : m->P.nq_u;
+#define LAUNCH(KER, p, q, w, ENRV, grid, lo_, nl_) \
+  hipLaunchKernelGGL((KER<p, q, w, ENRV>), dim3((unsigned)(grid)), dim3(kDdThreads), 0, s, A, lo_, nl_)
+#define X(p, q, w)                                                                              \
+  if (m->np_u == p && m->P.nq_u == q && nqw == w) {                                             \
+    if (nreg > 0) {                                                                             \
+      if (tau) LAUNCH(divdiv_tau_kernel, p, q, q, false, nreg, lo, nl);                         \
+      else LAUNCH(divdiv_apply_kernel, p, q, q, false, nreg, lo, nl);                           \
+      const int rc = check_hip(hipGetLastError(), "div-div kernel launch");                     \
+      if (rc) return rc;                                                                        \
+    }                                                                                           \
+    if (m->nenr > 0) {                                                                          \
+      if (tau) LAUNCH(divdiv_tau_kernel, p, q, w, true, m->nenr, 0, 0);                         \
+      else LAUNCH(divdiv_apply_kernel, p, q, w, true, m->nenr, 0, 0);                           \
+    }                                                                                           \
+    return check_hip(hipGetLastError(), "div-div kernel launch");                               \
+  }
+  DG_DD_COMBOS(X)
+#undef X
+#undef LAUNCH
+  return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: (k_u+1, nq_u, nq_wn) combination not compiled");
+}
+
+}  // namespace dgwm

@@ -1,0 +1,97 @@
+"""GPU div-div penalty and its per-cell tau_D (Sec. 4.2, eqs. div-div and
+tauD) against the FP64 CPU oracle, through the C ABI: 1e-12 of the largest
+entry (tau_D; polynomial and enrichment rows of D u separately)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1705_08813_amd import DgError, Mesh
+from paper_1705_08813_amd.inputs import PRESETS, MeshConfig, Workload, draw_inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+CASES = {
+    "tiny": PRESETS["tiny"].mesh,
+    "k2_stretched": MeshConfig(nx=3, ny=4, nz=2, gamma=1.3, k_u=2, nq_u=4, k_p=1, nq_p=2),
+    "k4_graded": MeshConfig(nx=5, ny=4, nz=3, gamma=1.8, k_u=4, nq_u=7, k_p=3, nq_p=4),
+    "k5": MeshConfig(nx=2, ny=3, nz=2, gamma=0.7, k_u=5, nq_u=8, k_p=4, nq_p=5),
+    "k4_lower_only": MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=4, nq_u=7, k_p=3, nq_p=4, enrich_upper=0),
+    "k3_plain": MeshConfig(nx=3, ny=3, nz=2, gamma=1.1, k_u=3, nq_u=5, k_p=2, nq_p=3, enrich_lower=0,
+                           enrich_upper=0),
+    "k2_periodic": MeshConfig(nx=3, ny=3, nz=2, k_u=2, nq_u=4, k_p=1, nq_p=2, fully_periodic=1),
+}
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_divdiv_matches_oracle(name):
+    cfg = CASES[name]
+    print(f"[gpu] div-div case={name}", flush=True)
+    inp = draw_inputs(Workload("dd", cfg, 31, 0.5, 1.5))
+    u_prev = np.random.default_rng(32).uniform(-1, 1, cfg.n_vel)
+    mesh = Mesh(cfg, inp["tau"])
+    td = mesh.divdiv_tau(torch.tensor(u_prev, device="cuda"), 0.37).cpu().numpy()
+    tdo = O.divdiv_tau(cfg, u_prev, 0.37, tau=inp["tau"])
+    assert _rel(td, tdo) <= TOL
+    d = mesh.apply_divdiv(torch.tensor(tdo, device="cuda"), torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    do = O.divdiv_apply(cfg, inp["u"], tdo, tau=inp["tau"])
+    n = cfg.ncell * 3 * (cfg.k_u + 1) ** 3
+    print(f"[gpu]   tau {_rel(td, tdo):.2e} poly {_rel(d[:n], do[:n]):.2e}", flush=True)
+    assert _rel(d[:n], do[:n]) <= TOL
+    if n < d.size:
+        assert _rel(d[n:], do[n:]) <= TOL
+
+
+def test_divdiv_large_mesh_sampled():
+    wl = PRESETS["large"]
+    cfg = wl.mesh
+    inp = draw_inputs(wl)
+    mesh = Mesh(cfg, inp["tau"])
+    u = torch.tensor(inp["u"], device="cuda")
+    td = mesh.divdiv_tau(u, 0.05)
+    d = mesh.apply_divdiv(td, u).cpu().numpy()
+    td = td.cpu().numpy()
+    rng = np.random.default_rng(9)
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    cells = set(rng.integers(0, cfg.ncell, 40).tolist())
+    for ey in (0, 1, ny - 2, ny - 1):
+        for _ in range(6):
+            cells.add(int(rng.integers(0, nx)) + nx * (ey + ny * int(rng.integers(0, nz))))
+    cells = np.array(sorted(cells), dtype=np.int64)
+    tdo = O.divdiv_tau(cfg, inp["u"], 0.05, tau=inp["tau"], cells=cells)
+    assert _rel(td[cells], tdo[cells]) <= TOL
+    do = O.divdiv_apply(cfg, inp["u"], td, tau=inp["tau"], cells=cells)
+    n3 = 3 * (cfg.k_u + 1) ** 3
+    rows = (cells[:, None] * n3 + np.arange(n3)[None, :]).ravel()
+    assert _rel(d[rows], do[rows]) <= TOL
+    off = cfg.ncell * n3
+    erows = []
+    for e in cells:
+        ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+        if ey in (0, ny - 1):
+            k = ex + nx * ((0 if ey == 0 else 1) + 2 * ez)
+            erows += [off + 3 * k + c for c in range(3)]
+    erows = np.array(erows)
+    assert _rel(d[erows], do[erows]) <= TOL
+
+
+def test_divdiv_rejects_bad_arguments():
+    mesh = Mesh(MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3))
+    u = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
+    with pytest.raises(DgError) as ei:
+        mesh.divdiv_tau(u, 0.1)
+    assert ei.value.code == -6
+    flat = Mesh(CASES["tiny"])
+    uf = torch.zeros(flat.n_vel, dtype=torch.float64, device="cuda")
+    with pytest.raises(DgError) as ei:
+        flat.divdiv_tau(uf, float("nan"))
+    assert ei.value.code == -1
+    with pytest.raises(DgError) as ei:
+        flat.apply_divdiv(torch.ones(flat.n_cells, dtype=torch.float64, device="cuda"), uf, uf)
+    assert ei.value.code == -1
