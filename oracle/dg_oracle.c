@@ -919,8 +919,9 @@ static void grad_cell(const ctx *C, const double *p, int64_t e, double *g, doubl
 
 /* Velocity divergence term for every pressure test function q of cell e:
  *   c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e},  {{u}} = (u- + u+)/2,
- * u the full (enriched) velocity, with the external value u+ = -u- on no-slip
- * walls (so {{u}} = 0 there) and the velocity quadrature of the cell and of
+ * u the full (enriched) velocity; on no-slip walls the interior value
+ * {{u}} = u- (the boundary condition Sec. 4.2 gives for this term of the
+ * pressure Poisson equation), and the velocity quadrature of the cell and of
  * its faces.  Out: pressure layout. */
 static void div_cell(const ctx *C, const double *u, int64_t e, double *out, double *bv, double (*bg)[3],
                      double *bv2, double (*bg2)[3], double *pv, double (*pg)[3]) {
@@ -946,7 +947,6 @@ static void div_cell(const ctx *C, const double *u, int64_t e, double *out, doub
     int d = f / 2, s = f % 2;
     int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
     int64_t nb = face_neighbor(C, e, d, s);
-    if (nb < 0) continue; /* {{u}} = 0 on a no-slip wall */
     const double *q1, *w1, *q2, *w2;
     int n1, n2;
     face_rule(C, e, nb, t1, t2, &q1, &w1, &n1, &q2, &w2, &n2);
@@ -963,10 +963,14 @@ static void div_cell(const ctx *C, const double *u, int64_t e, double *out, doub
         double wf = det * nr * w1[a] * w2[b];
         vel_pt pm, pp;
         eval_vel(C, u, e, xi, Ji, 0, &pm, bv, bg);
-        xn[d] = 1 - s; xn[t1] = xi[t1]; xn[t2] = xi[t2];
-        cell_map(C, nb, xn, Xn, Jn);
-        inv3(Jn, Jin);
-        eval_vel(C, u, nb, xn, Jin, 0, &pp, bv2, bg2);
+        if (nb >= 0) {
+          xn[d] = 1 - s; xn[t1] = xi[t1]; xn[t2] = xi[t2];
+          cell_map(C, nb, xn, Xn, Jn);
+          inv3(Jn, Jin);
+          eval_vel(C, u, nb, xn, Jin, 0, &pp, bv2, bg2);
+        } else {
+          pp = pm; /* interior value on a no-slip wall */
+        }
         double un = 0;
         for (int k = 0; k < 3; ++k) un += 0.5 * (pm.u[k] + pp.u[k]) * nv[k];
         basis3(np, C->glp, xi, Ji, pv, pg);

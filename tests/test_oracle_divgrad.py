@@ -2,9 +2,13 @@
 velocity divergence term C (pressure test functions) of Sec. 4.2.
 
 - Discrete adjoint: q^T C u = -u^T P q.  Integrating the volume terms by parts
-  leaves only face terms that cancel between neighbours and, with the wall's
-  external values (u+ = -u-, p+ = p-), on the walls; this is exact to rounding
-  where the rules integrate div(q u) exactly (cells without enrichment).
+  leaves face terms that cancel between neighbours; with the interior wall
+  values of both terms (u+ = u-, p+ = p-) the walls leave the flux of q u . n,
+  which vanishes for a q that is zero on the walls (a fully periodic mesh has
+  none).  Exact to rounding where the rules integrate div(q u) exactly (cells
+  without enrichment).
+- A constant velocity has C u = 0: with the interior wall value the wall faces
+  close the integration by parts (the mirror value would leave -q u . n).
 - Divergence-free fields tangential to the walls have C u = 0: a channel
   profile in the polynomial space, and psi(y) e_x in the enriched layer (psi
   depends on y only for a constant tau_w; integration by parts along x is
@@ -26,18 +30,30 @@ PLAIN = [MeshConfig(nx=3, ny=4, nz=2, gamma=1.2, k_u=3, k_p=2, nq_u=5, nq_p=3, e
          MeshConfig(nx=3, ny=3, nz=2, k_u=2, k_p=1, nq_u=4, nq_p=2, fully_periodic=1)]
 
 
+def _zero_on_walls(cfg, q):
+    """q with the node layers on the wall faces (y = -1, y = +1) set to zero."""
+    if cfg.fully_periodic:
+        return q
+    n = cfg.k_p + 1
+    qr = q.reshape(cfg.nz, cfg.ny, cfg.nx, n, n, n).copy()   # [ez][ey][ex][k][j][i]
+    qr[:, 0, :, :, 0, :] = 0.0
+    qr[:, cfg.ny - 1, :, :, n - 1, :] = 0.0
+    return qr.reshape(-1)
+
+
 @pytest.mark.parametrize("cfg", PLAIN)
 def test_divergence_is_minus_gradient_transpose(cfg):
     rng = np.random.default_rng(5)
     u = rng.uniform(-1, 1, cfg.n_vel)
-    q = rng.uniform(-1, 1, cfg.n_p)
+    q = _zero_on_walls(cfg, rng.uniform(-1, 1, cfg.n_p))
     tau = np.ones(cfg.n_tau)
     a = q @ O.velocity_divergence(cfg, u, tau=tau)
     b = u @ O.pressure_gradient(cfg, q, tau=tau)
     scale = np.abs(q) @ np.abs(O.velocity_divergence(cfg, np.abs(u), tau=tau))
     assert abs(a + b) <= 1e-13 * max(scale, 1.0), (a, b)
-    # and column by column on a few unit vectors
-    for i in rng.integers(0, cfg.n_p, 4):
+    # and column by column on a few unit vectors (off the walls)
+    cand = np.nonzero(_zero_on_walls(cfg, np.ones(cfg.n_p)))[0]
+    for i in rng.choice(cand, 4, replace=False):
         ei = np.zeros(cfg.n_p)
         ei[i] = 1.0
         gi = O.pressure_gradient(cfg, ei, tau=tau)
@@ -70,6 +86,16 @@ def test_channel_profile_is_divergence_free(k):
     c = O.velocity_divergence(cfg, u, tau=np.ones(cfg.n_tau))
     ref = O.velocity_divergence(cfg, np.abs(u), tau=np.ones(cfg.n_tau))
     assert np.abs(c).max() <= 1e-13 * max(np.abs(ref).max(), 1.0)
+
+
+@pytest.mark.parametrize("cfg", [PLAIN[0], MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=3, k_p=2, nq_u=5, nq_p=3)])
+def test_constant_velocity_has_zero_divergence(cfg):
+    u = _nodal(cfg, lambda x, y, z: (0.3 + 0 * y, 1.0 + 0 * y, -0.5 + 0 * y))
+    c = O.velocity_divergence(cfg, u, tau=np.ones(cfg.n_tau))
+    scale = O.velocity_divergence(cfg, np.abs(u), tau=np.ones(cfg.n_tau))
+    # the wall-normal component alone has a nonzero divergence term per cell (sanity of the scale)
+    c_y = O.velocity_divergence(cfg, _nodal(cfg, lambda x, y, z: (0 * y, y, 0 * y)), tau=np.ones(cfg.n_tau))
+    assert np.abs(c).max() <= 1e-13 * max(np.abs(scale).max(), np.abs(c_y).max())
 
 
 def test_enrichment_along_x_is_divergence_free():
