@@ -245,7 +245,7 @@ int dg_apply_inverse_mass(const dg_mesh* mesh, const double* r, double* x, void*
  *   g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}
  * for every velocity test function v (N_B e_c, and psi e_c in enriched
  * cells), {{p}} the central average of the two traces, on no-slip walls the
- * external value p+ = p-.  Velocity quadrature of the cell (nq_u^3, nq_u x
+ * interior value {{p}} = p- (Sec. 4.2, projection step).  Velocity quadrature of the cell (nq_u^3, nq_u x
  * nq_wn x nq_u in enriched cells) and of its faces.  Flat meshes only.
  *   p: device, dg_num_dofs(mesh, 1) doubles; g: device, dg_num_dofs(mesh, 0)
  *   doubles (velocity layout, enrichment rows included), distinct from p.
@@ -256,9 +256,10 @@ int dg_apply_pressure_gradient(const dg_mesh* mesh, const double* p, double* g, 
 /* Velocity divergence term (paper Sec. 4.2):
  *   c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}
  * for every pressure test function q, u the full velocity (psi u~ included),
- * on no-slip walls the external value u+ = -u- (so {{u}} = 0 there); the
- * same quadrature as the gradient, so that c = -P^T u wherever the rules
- * integrate div(q u) exactly.  Flat meshes only.
+ * on no-slip walls the interior value {{u}} = u- (Sec. 4.2, the boundary
+ * condition of this term in the pressure Poisson equation); the same
+ * quadrature as the gradient, so that q^T C u = -u^T P q wherever the rules
+ * integrate div(q u) exactly and q vanishes on the walls.  Flat meshes only.
  *   u: device, dg_num_dofs(mesh, 0) doubles; c: device, dg_num_dofs(mesh, 1)
  *   doubles (pressure layout), distinct from u.
  *   Errors: as for dg_apply_pressure_gradient. */

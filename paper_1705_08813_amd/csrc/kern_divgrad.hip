@@ -4,8 +4,9 @@
 //   P: g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}     (velocity test functions)
 //   C: c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}    (pressure test functions)
 //
-// {{.}} the central average; on no-slip walls the external values are
-// p+ = p- and u+ = -u- (so {{u}} = 0 there).  u is the full velocity with
+// {{.}} the central average; on no-slip walls both terms take the interior
+// value, p+ = p- and u+ = u- (the boundary conditions Sec. 4.2 gives for the
+// pressure Poisson equation and the projection step).  u is the full velocity with
 // psi u~ in enriched cells, and the velocity test functions include psi e_c.
 // Both use the velocity quadrature of the cell (nq^3, nq x nqy x nq in
 // enriched cells) and of its faces (x- and z-faces take the cell's
@@ -113,7 +114,7 @@ using MD = ct::MatSd<NP, NQ>;
 // ---------------------------------------------------------------------------
 // Velocity divergence: out = C u (pressure layout).
 
-// Faces of direction D: {{u_D}} n_D at the face points, integrated against
+// Faces of direction D: {{u_D}} n_D at the face points (u_D- on walls), integrated against
 // the pressure face layer, accumulated into acc.
 template <int NPU, int NPP, int NQ, int NQY, bool ENR, int D>
 __device__ __forceinline__ void div_faces(const DgArgs& A, const CellGeo& g, const double* su, const double* nl,
@@ -138,15 +139,16 @@ __device__ __forceinline__ void div_faces(const DgArgs& A, const CellGeo& g, con
   for (int it = tid; it < 2 * Q1 * Q2; it += kDgThreads) {
     const int s = it / (Q1 * Q2), pt = it - s * Q1 * Q2;
     const int q1 = pt % Q1, q2 = pt / Q1;
-    double f = 0.0;
+    double um = w0[(s * 2) * Q1 * Q2 + pt], up = um;  // interior value on a no-slip wall
+    if (ENR) um += A.psi[(g.enr * A.psi_pts + A.psi_off[1 + 2 * D + s] + pt) * 4] * ut[D];
     if (nbf[2 * D + s] >= 0) {
-      double um = w0[(s * 2) * Q1 * Q2 + pt], up = w0[(s * 2 + 1) * Q1 * Q2 + pt];
-      if (ENR) um += A.psi[(g.enr * A.psi_pts + A.psi_off[1 + 2 * D + s] + pt) * 4] * ut[D];
+      up = w0[(s * 2 + 1) * Q1 * Q2 + pt];
       const int64_t ne = nbe[2 * D + s];
       if (ne >= 0) up += A.psi[(ne * A.psi_pts + A.psi_off[1 + 2 * D + (1 - s)] + pt) * 4] * utn[2 * D + s];
-      f = tb1.w[q1] * tb2.w[q2] * area * (s ? 0.5 : -0.5) * (um + up);
+    } else {
+      up = um;
     }
-    w1[it] = f;
+    w1[it] = tb1.w[q1] * tb2.w[q2] * area * (s ? 0.5 : -0.5) * (um + up);
   }
   __syncthreads();
   sweep_c<0, Q1, Q2, 1, NPP, true, false, MS<NPP, Q1>>(w1, Q1 * Q2, w0, NPP * Q2, 1.0, 2);
