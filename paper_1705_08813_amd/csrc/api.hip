@@ -380,6 +380,8 @@ int dg_wall_shear_nodes(const dg_mesh* m, const double* u, double* tau_nodes, vo
   if (!m || !u || !tau_nodes) return set_error(DG_ERR_ARG, "mesh/u/tau_nodes is NULL");
   if (m->curved || m->P.fully_periodic)
     return set_error(DG_ERR_UNSUPPORTED, "nodal wall shear stress: flat no-slip walls only");
+  if (static_cast<const void*>(u) == static_cast<const void*>(tau_nodes))
+    return set_error(DG_ERR_ARG, "u and tau_nodes must not alias");
   if (!aligned256(u) || !aligned256(tau_nodes)) return set_error(DG_ERR_ARG, "u and tau_nodes must be 256-byte aligned");
   return launch_wall_shear_nodes(m, u, tau_nodes, static_cast<hipStream_t>(stream));
 }
@@ -415,6 +417,7 @@ int dg_apply_inverse_mass(const dg_mesh* m, const double* r, double* x, void* st
 int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, void* stream) {
   if (!m || !p || !g) return set_error(DG_ERR_ARG, "mesh/p/g is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "pressure gradient: flat meshes only");
+  if (static_cast<const void*>(p) == static_cast<const void*>(g)) return set_error(DG_ERR_ARG, "p and g must not alias");
   if (!aligned256(p) || !aligned256(g)) return set_error(DG_ERR_ARG, "p and g must be 256-byte aligned");
   return launch_divgrad(m, false, p, g, static_cast<hipStream_t>(stream));
 }
@@ -422,6 +425,7 @@ int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, voi
 int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, void* stream) {
   if (!m || !u || !c) return set_error(DG_ERR_ARG, "mesh/u/c is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "velocity divergence: flat meshes only");
+  if (static_cast<const void*>(u) == static_cast<const void*>(c)) return set_error(DG_ERR_ARG, "u and c must not alias");
   if (!aligned256(u) || !aligned256(c)) return set_error(DG_ERR_ARG, "u and c must be 256-byte aligned");
   return launch_divgrad(m, true, u, c, static_cast<hipStream_t>(stream));
 }
@@ -430,6 +434,7 @@ int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* 
   if (!m || !u || !tau_d) return set_error(DG_ERR_ARG, "mesh/u/tau_d is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
   if (!(dt_over_cr >= 0) || !std::isfinite(dt_over_cr)) return set_error(DG_ERR_ARG, "dt/Cr must be >= 0 and finite");
+  if (static_cast<const void*>(u) == static_cast<const void*>(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must not alias");
   if (!aligned256(u) || !aligned256(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must be 256-byte aligned");
   return launch_divdiv(m, true, u, nullptr, dt_over_cr, tau_d, static_cast<hipStream_t>(stream));
 }

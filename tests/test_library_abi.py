@@ -54,6 +54,15 @@ def test_null_handles_are_rejected():
     assert L.dg_apply_velocity_residual(None, 0, None, None, None) == -1
     assert L.dg_apply_poisson(None, 0, None, None, None) == -1
     assert L.dg_poisson_diagonal(None, None, None) == -1
+    assert L.dg_wall_shear_nodes(None, None, None, None) == -1
+    assert L.dg_update_wall_shear_nodes(None, None, None) == -1
+    assert L.dg_project_velocity(None, None, None, None) == -1
+    assert L.dg_enrichment_active(None, None, None) == -1
+    assert L.dg_apply_inverse_mass(None, None, None, None) == -1
+    assert L.dg_apply_pressure_gradient(None, None, None, None) == -1
+    assert L.dg_apply_velocity_divergence(None, None, None, None) == -1
+    assert L.dg_divdiv_tau(None, None, 0.0, None, None) == -1
+    assert L.dg_apply_divdiv(None, None, None, None, None) == -1
 
 
 def test_large_workspace_fits_hbm():
