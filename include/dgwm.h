@@ -23,7 +23,10 @@
  *    handle holds one small pinned host buffer (freed by dg_destroy_mesh).
  *  - Calls on different mesh handles may run concurrently from different
  *    threads; two solves on one handle must not overlap (the handle caches
- *    eigenvalue estimates and stages the solver's scalars).
+ *    eigenvalue estimates and stages the solver's scalars), and a wall-shear
+ *    update (dg_update_wall_shear, dg_update_wall_shear_nodes) must not
+ *    overlap any other call on its handle: it swaps the handle's current and
+ *    previous psi tables and invalidates its inverse-mass cache.
  *
  * Mesh and numbering
  * ------------------

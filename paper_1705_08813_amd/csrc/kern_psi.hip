@@ -97,10 +97,13 @@ struct CellRef {
   bool lower;
 };
 
-__device__ __forceinline__ CellRef enriched_cell(const PsiArgs& A, int64_t enr) {
+// (the enriched count stays below 2^31 like the cell count, so 32-bit
+// division suffices)
+__device__ __forceinline__ CellRef enriched_cell(const PsiArgs& A, int64_t enr64) {
   CellRef c;
-  c.ex = (int)(enr % A.nx);
-  const int64_t t0 = enr / A.nx;
+  const int enr = (int)enr64;
+  c.ex = enr % A.nx;
+  const int t0 = enr / A.nx;
   const int slot = (int)(t0 % A.nslots);
   c.ez = (int)(t0 / A.nslots);
   c.lower = (slot == A.lower_slot);
@@ -230,8 +233,9 @@ template <int NQ, int NQY>
 __global__ void psi_kernel(const PsiArgs A) {
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gid >= A.nenr * A.psi_pts) return;
-  const int64_t enr = gid / A.psi_pts;
-  const int pt = (int)(gid - enr * A.psi_pts);
+  constexpr int PTS = psi_points(NQ, NQY);  // == A.psi_pts; a constant divisor
+  const int64_t enr = gid / PTS;
+  const int pt = (int)(gid - enr * PTS);
   double* o = A.psi + gid * 4;
   if (!A.act[enr]) {
     o[0] = o[1] = o[2] = o[3] = 0.0;
