@@ -70,6 +70,7 @@ def lib():
         L.orc_psi_point_nodal.argtypes = [P, _D, ctypes.c_int64, _D, _D]
         L.orc_wall_shear_nodes.argtypes = [P, _D, _D, _D, _D]
         L.orc_psi_volume.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D]
+        L.orc_psi_volume4.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_pressure_gradient.argtypes = [P, _D, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_divdiv_tau.argtypes = [P, _D, _D, _D, ctypes.c_double, _I64, ctypes.c_int64, _D]
         L.orc_divdiv_apply.argtypes = [P, _D, _D, _D, _D, _I64, ctypes.c_int64, _D]
@@ -344,6 +345,22 @@ def divdiv_apply(cfg, u, tau_d, tau=None, tau_nodes=None, cells=None):
                                 cells.size, _ptr(out))
     if rc:
         raise RuntimeError(f"orc_divdiv_apply failed: {rc}")
+    return out
+
+
+def psi_volume4(cfg, cells, tau=None, tau_nodes=None):
+    """psi and grad psi at the enriched volume rule points of the listed
+    enriched cells: [len(cells)][points][4]."""
+    p = params(cfg)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    out = np.zeros((cells.size, p.nq_u * p.nq_wn * p.nq_u, 4))
+    rc = lib().orc_psi_volume4(ctypes.byref(p), _ptr(t) if t is not None else None,
+                               _ptr(tn) if tn is not None else None, cells.ctypes.data_as(_I64), cells.size,
+                               _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_psi_volume4 failed: {rc}")
     return out
 
 

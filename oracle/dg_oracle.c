@@ -1309,8 +1309,22 @@ int orc_psi_point_nodal(const orc_params *P, const double *tau_nodes, int64_t e,
 /* psi at the points of the enriched volume rule (nq_u x nq_wn x nq_u, x
  * fastest) of each listed enriched cell, from the per-point tau_w or, when
  * given, the nodal tau_nodes; out: [ncells][points]. */
+static int psi_volume(const orc_params *P, const double *tau_w, const double *tau_nodes, const int64_t *cells,
+                      int64_t ncells, double *out, int with_grad);
+
 int orc_psi_volume(const orc_params *P, const double *tau_w, const double *tau_nodes, const int64_t *cells,
                    int64_t ncells, double *out) {
+  return psi_volume(P, tau_w, tau_nodes, cells, ncells, out, 0);
+}
+
+/* The same with grad psi: out [ncells][points][psi, dpsi/dx, dpsi/dy, dpsi/dz]. */
+int orc_psi_volume4(const orc_params *P, const double *tau_w, const double *tau_nodes, const int64_t *cells,
+                    int64_t ncells, double *out) {
+  return psi_volume(P, tau_w, tau_nodes, cells, ncells, out, 1);
+}
+
+static int psi_volume(const orc_params *P, const double *tau_w, const double *tau_nodes, const int64_t *cells,
+                      int64_t ncells, double *out, int with_grad) {
   ctx C;
   if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
@@ -1332,7 +1346,13 @@ int orc_psi_volume(const orc_params *P, const double *tau_w, const double *tau_n
           inv3(J, Ji);
           psi_pt pt;
           eval_psi(&C, e, xi, Ji, &pt);
-          out[i * npts + a + nq * (b + nw * c)] = pt.psi;
+          const int64_t o = i * npts + a + nq * (b + nw * c);
+          if (with_grad) {
+            out[o * 4] = pt.psi;
+            for (int d = 0; d < 3; ++d) out[o * 4 + 1 + d] = pt.g[d];
+          } else {
+            out[o] = pt.psi;
+          }
         }
   }
   ctx_free(&C);

@@ -145,3 +145,71 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
             else:
                 x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = np.linalg.solve(M, rp)
     return (x, conds) if return_cond else x
+
+
+def _basis_grad_at(cfg, pts, h):
+    """Physical gradients of N_B at the points: array (npts, n^3, 3)."""
+    n = cfg.k_u + 1
+    nodes = gauss_lobatto(n)
+    G = np.zeros((len(pts), n ** 3, 3))
+    for q, (x, y, z) in enumerate(pts):
+        (vx, dx), (vy, dy), (vz, dz) = lagrange(nodes, x), lagrange(nodes, y), lagrange(nodes, z)
+        G[q, :, 0] = np.einsum("m,j,i->mji", vz, vy, dx).reshape(-1) / h[0]
+        G[q, :, 1] = np.einsum("m,j,i->mji", vz, dy, vx).reshape(-1) / h[1]
+        G[q, :, 2] = np.einsum("m,j,i->mji", dz, vy, vx).reshape(-1) / h[2]
+    return G
+
+
+def projection_step(cfg, u_hat, g, scale, tau_d, psi4):
+    """The element-wise projection step of the dual-splitting scheme (Sec.
+    4.2, eq. projectionspat):  M_e(v, x) + D_e(v, x) = M_e(v, u_hat) - scale P_e(v, p)
+    for every velocity test function v of every cell, with g = P p given
+    (velocity layout) and D_e the div-div penalty (div v, tau_D,e div x)_e.
+    Per cell the matrix M_e + D_e over the cell's local basis (3 components
+    of N_B, plus psi e_c while the enrichment is on; the cell's velocity
+    rule) is assembled from 3-D basis values and gradients and the system is
+    solved densely.  psi4: [nenr][npts][4] psi and grad psi at the enriched
+    volume rule.  Flat (box) meshes only."""
+    if cfg.wall_amp != 0.0:
+        raise ValueError("flat meshes only")
+    n3 = (cfg.k_u + 1) ** 3
+    u_hat = np.asarray(u_hat, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    x = np.zeros_like(u_hat)
+    eta = vertex_eta(cfg)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    off = cfg.ncell * 3 * n3
+    enr = {int(e): k for k, e in enumerate(enriched_cells(cfg))}
+    pts_e, wts_e = volume_rule(cfg)
+    pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
+    V_e, V_r = basis_at(cfg, pts_e), basis_at(cfg, pts_r)
+    for e in range(cfg.ncell):
+        ey = (e // cfg.nx) % cfg.ny
+        h = (hx, eta[ey + 1] - eta[ey], hz)
+        detJ = h[0] * h[1] * h[2]
+        k = enr.get(e)
+        pts, wts, V = (pts_e, wts_e, V_e) if k is not None else (pts_r, wts_r, V_r)
+        G = _basis_grad_at(cfg, pts, h)
+        w = wts * detJ
+        on = k is not None and bool(np.any(psi4[k][:, 0] != 0.0))
+        nb = 3 * n3 + (3 if on else 0)
+        # values (npts, 3, nb) and divergences (npts, nb) of the local basis
+        val = np.zeros((len(pts), 3, nb))
+        div = np.zeros((len(pts), nb))
+        for c in range(3):
+            val[:, c, c * n3:(c + 1) * n3] = V
+            div[:, c * n3:(c + 1) * n3] = G[:, :, c]
+            if on:
+                val[:, c, 3 * n3 + c] = psi4[k][:, 0]
+                div[:, 3 * n3 + c] = psi4[k][:, 1 + c]
+        M = np.einsum("q,qci,qcj->ij", w, val, val)
+        D = tau_d[e] * np.einsum("q,qi,qj->ij", w, div, div)
+        # right-hand side: M u_hat - scale g
+        coef = np.concatenate([u_hat[e * 3 * n3:(e + 1) * 3 * n3]] + ([u_hat[off + 3 * k: off + 3 * k + 3]] if on else []))
+        rhs = M @ coef - scale * np.concatenate([g[e * 3 * n3:(e + 1) * 3 * n3]] +
+                                                ([g[off + 3 * k: off + 3 * k + 3]] if on else []))
+        sol = np.linalg.solve(M + D, rhs)
+        x[e * 3 * n3:(e + 1) * 3 * n3] = sol[:3 * n3]
+        if k is not None:
+            x[off + 3 * k: off + 3 * k + 3] = sol[3 * n3:] if on else 0.0
+    return x
