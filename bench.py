@@ -371,7 +371,22 @@ def main():
         t_dd = ev7[1].elapsed_time(ev7[2]) / nrep
         extras["divdiv"] = {"tau_ms": ev7[0].elapsed_time(ev7[1]) / nrep, "apply_ms": t_dd,
                             "apply_GBps_alg": 16.0 * n_vel / (t_dd * 1e-3) / 1e9}
-        del gv, cp, td
+        # element-wise projection step (M + D) x = M u_hat - dt P p, per-cell PCG to 1e-14:
+        # u_hat, P p in, x out (24 B per unknown); the cost is the per-cell iterations
+        mesh.apply_pressure_gradient(p, gv)
+        xs = torch.empty_like(u)
+        for _ in range(2):
+            mesh.projection_step(td, u, gv, 1e-3, xs)
+        ev8 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        nps = max(3, nrep // 4)
+        ev8[0].record(stream)
+        for _ in range(nps):
+            mesh.projection_step(td, u, gv, 1e-3, xs)
+        ev8[1].record(stream)
+        torch.cuda.synchronize()
+        t_ps = ev8[0].elapsed_time(ev8[1]) / nps
+        extras["projection_step"] = {"ms": t_ps, "GBps_alg": 24.0 * n_vel / (t_ps * 1e-3) / 1e9}
+        del gv, cp, td, xs
     if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)

@@ -286,6 +286,26 @@ int dg_divdiv_tau(const dg_mesh* mesh, const double* u, double dt_over_cr, doubl
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
 int dg_apply_divdiv(const dg_mesh* mesh, const double* tau_d, const double* u, double* out, void* stream);
 
+/* Element-wise projection step of the dual-splitting scheme (paper Sec. 4.2,
+ * eq. projectionspat), cell by cell:
+ *   (M_e + D_e) x = M_e u_hat - scale g,
+ * M_e the velocity mass matrix and D_e the div-div penalty with tau_d (as in
+ * dg_apply_inverse_mass and dg_apply_divdiv), g = P p the pressure gradient
+ * term (dg_apply_pressure_gradient; with scale = dt/gamma_0 this is the
+ * projection u^ - dt/gamma_0 grad p of the paper's scheme).  Each cell solves
+ * its block by conjugate gradients preconditioned with its own M_e^{-1},
+ * until (r, M^{-1} r) has fallen by 1e-28 or after 200 iterations.  The cap
+ * binds only for tau_D,e / h^2 far beyond the scale of eq. tauD (Courant
+ * numbers well above one), where the preconditioned block's condition number
+ * grows like tau_D k^4 / h^2; the result is then the last iterate.
+ *   tau_d: device, nx*ny*nz doubles; u_hat, g, x: device, dg_num_dofs(mesh,
+ *   0) doubles, x distinct from u_hat and g.  Flat meshes only.  Fills the
+ *   inverse-mass cache on its first call after a wall-shear update (see
+ *   dg_apply_inverse_mass).
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
+int dg_projection_step(const dg_mesh* mesh, const double* tau_d, const double* u_hat, const double* g, double scale,
+                       double* x, void* stream);
+
 /* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
  * term, flux eq. ipflux) with homogeneous Neumann data on the walls:
  *   (A p)(q) = sum_e (grad q, grad p)_e + sum_{interior F} [ -1/2 (grad q.n)(p- - p+)

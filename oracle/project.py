@@ -160,7 +160,7 @@ def _basis_grad_at(cfg, pts, h):
     return G
 
 
-def projection_step(cfg, u_hat, g, scale, tau_d, psi4):
+def projection_step(cfg, u_hat, g, scale, tau_d, psi4, cells=None):
     """The element-wise projection step of the dual-splitting scheme (Sec.
     4.2, eq. projectionspat):  M_e(v, x) + D_e(v, x) = M_e(v, u_hat) - scale P_e(v, p)
     for every velocity test function v of every cell, with g = P p given
@@ -169,7 +169,8 @@ def projection_step(cfg, u_hat, g, scale, tau_d, psi4):
     of N_B, plus psi e_c while the enrichment is on; the cell's velocity
     rule) is assembled from 3-D basis values and gradients and the system is
     solved densely.  psi4: [nenr][npts][4] psi and grad psi at the enriched
-    volume rule.  Flat (box) meshes only."""
+    volume rule.  cells: optional subset of cells to solve (others stay 0).
+    Flat (box) meshes only."""
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -183,7 +184,7 @@ def projection_step(cfg, u_hat, g, scale, tau_d, psi4):
     pts_e, wts_e = volume_rule(cfg)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     V_e, V_r = basis_at(cfg, pts_e), basis_at(cfg, pts_r)
-    for e in range(cfg.ncell):
+    for e in (range(cfg.ncell) if cells is None else (int(c) for c in cells)):
         ey = (e // cfg.nx) % cfg.ny
         h = (hx, eta[ey + 1] - eta[ey], hz)
         detJ = h[0] * h[1] * h[2]

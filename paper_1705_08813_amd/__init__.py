@@ -203,6 +203,19 @@ class Mesh:
         _lib.check(_lib.lib().dg_apply_divdiv(self.handle, _dptr(tau_d), _dptr(u), _dptr(out), _stream_ptr(stream)))
         return out
 
+    def projection_step(self, tau_d, u_hat, g, scale, x=None, stream=None):
+        """Element-wise projection step (Sec. 4.2): (M + D) x = M u_hat - scale g."""
+        import torch
+        self._check_f64(tau_d, self.n_cells, "tau_d")
+        self._check_f64(u_hat, self.n_vel, "u_hat")
+        self._check_f64(g, self.n_vel, "g")
+        if x is None:
+            x = torch.empty_like(u_hat)
+        self._check_f64(x, self.n_vel, "x")
+        _lib.check(_lib.lib().dg_projection_step(self.handle, _dptr(tau_d), _dptr(u_hat), _dptr(g), float(scale),
+                                                 _dptr(x), _stream_ptr(stream)))
+        return x
+
     def enrichment_active(self, stream=None):
         """Activity flags (int32 device tensor, 1 on / 0 switched off) of the
         enriched cells in the current space."""

@@ -65,6 +65,7 @@ _SIGS = {
     "dg_apply_velocity_divergence": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "dg_divdiv_tau": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP]),
     "dg_apply_divdiv": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "dg_projection_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     "dg_enrichment_active": (ctypes.c_int, [_VP, _VP, _VP]),
     "dg_num_dofs": (ctypes.c_int64, [_VP, ctypes.c_int]),
     "dg_num_enriched": (ctypes.c_int64, [_VP]),

@@ -25,6 +25,10 @@ struct WsLayout {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// per-cell CG of the projection step: stop when (r, M^{-1} r) fell by rtol^2
+constexpr int kProjStepMaxIt = 200;
+constexpr double kProjStepRtol = 1e-14;
+
 // Inverse of the 1-D mass matrix M_ij = sum_q w_q N_i(g_q) N_j(g_q) of a
 // Gauss rule with nq >= np points (symmetric positive definite), by
 // Gauss-Jordan elimination with partial pivoting; S is [nq][np], out [np][np].
@@ -156,7 +160,7 @@ WsLayout layout(const dg_mesh& m) {
   L.act = o; o = up256(o + sizeof(int32_t) * (size_t)m.nenr);
   L.act_prev = o; o = up256(o + sizeof(int32_t) * (size_t)m.nenr);
   L.minv = o; o = up256(o + sizeof(double) * 2 * m.np_u * m.np_u);
-  L.apoly = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (m.np_u * m.np_u * m.np_u + 1));
+  L.apoly = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (2 * m.np_u * m.np_u * m.np_u + 2));
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
   L.diag32 = o; o = up256(o + sizeof(float) * m.n_p);
   L.geo = o; o = up256(o + sizeof(double) * 10 * (size_t)m.ncell * m.geo_stride);
@@ -446,6 +450,18 @@ int dg_apply_divdiv(const dg_mesh* m, const double* tau_d, const double* u, doub
   if (!aligned256(u) || !aligned256(out) || !aligned256(tau_d))
     return set_error(DG_ERR_ARG, "tau_d, u and out must be 256-byte aligned");
   return launch_divdiv(m, false, u, tau_d, 0.0, out, static_cast<hipStream_t>(stream));
+}
+
+int dg_projection_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
+                       double* x, void* stream) {
+  if (!m || !tau_d || !u_hat || !g || !x) return set_error(DG_ERR_ARG, "mesh/tau_d/u_hat/g/x is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "projection step: flat meshes only");
+  if (!std::isfinite(scale)) return set_error(DG_ERR_ARG, "scale must be finite");
+  if (x == u_hat || x == g) return set_error(DG_ERR_ARG, "x must not alias u_hat or g");
+  if (!aligned256(tau_d) || !aligned256(u_hat) || !aligned256(g) || !aligned256(x))
+    return set_error(DG_ERR_ARG, "tau_d, u_hat, g and x must be 256-byte aligned");
+  return launch_projection_step(m, tau_d, u_hat, g, scale, x, kProjStepMaxIt, kProjStepRtol,
+                                static_cast<hipStream_t>(stream));
 }
 
 int dg_enrichment_active(const dg_mesh* m, int32_t* flags, void* stream) {

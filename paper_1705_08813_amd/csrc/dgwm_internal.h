@@ -153,7 +153,7 @@ struct dg_mesh {
   int32_t* act;           // [enr] enrichment on (1) or switched off (0)
   int32_t* act_prev;      // the same flags before the last wall-shear update
   double* minv;           // inverse 1-D mass matrices [2][np_u][np_u]: x/z rule, wall-normal rule
-  double* apoly;          // [enr][np_u^3 + 1]: polynomial part of the current psi (inverse mass cache)
+  double* apoly;          // [enr][2 np_u^3 + 2]: polynomial part of the current psi (inverse mass / projection step cache)
   mutable int apoly_ok = 0;  // apoly matches the current psi table
   double* diag;           // Poisson diagonal (FP64)
   float* diag32;          // Poisson diagonal (FP32 copy)
@@ -221,6 +221,9 @@ int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau
                   hipStream_t s);
 // out = C u (divergence, pressure layout) or P p (gradient, velocity layout), flat meshes
 int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s);
+// element-wise projection step: (M + D) x = M u_hat - scale g per cell, preconditioned CG in each cell
+int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
+                           double* x, int max_it, double rtol, hipStream_t s);
 // x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)
 int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s);
 // u_new = L2 projection of u_old from the space of psi_prev onto that of psi
