@@ -155,6 +155,10 @@ struct dg_mesh {
   double* minv;           // inverse 1-D mass matrices [2][np_u][np_u]: x/z rule, wall-normal rule
   double* apoly;          // [enr][2 np_u^3 + 2]: polynomial part of the current psi (inverse mass / projection step cache)
   mutable int apoly_ok = 0;  // apoly matches the current psi table
+  double* spec;           // projection step, cells without enrichment: [3][np][np] 1-D factors, then per
+                          // distinct layer height Z, Z^T, lambda of the whitened div-div form, then the
+                          // int32 layer -> slot map (filled on the first projection step)
+  mutable int spec_ok = 0;   // spec filled
   double* diag;           // Poisson diagonal (FP64)
   float* diag32;          // Poisson diagonal (FP32 copy)
   double* hy;             // ny cell heights, then their ny reciprocals
@@ -222,6 +226,13 @@ int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau
 // out = C u (divergence, pressure layout) or P p (gradient, velocity layout), flat meshes
 int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s);
 // element-wise projection step: (M + D) x = M u_hat - scale g per cell, preconditioned CG in each cell
+// projection step: spectral tables of every layer (direct solves)
+int spectral_layers(const dg_mesh& m, std::vector<int>* map, std::vector<double>* heights);
+size_t spectral_table_doubles(const dg_mesh& m);
+int ensure_spectral_tables(const dg_mesh* m, hipStream_t s);  // host eigendecompositions on first use
+void spectral_pointers(const dg_mesh* m, const double** mats, const double** slots, const int32_t** map);
+int launch_spectral_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
+                         double* x, hipStream_t s);
 int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
                            double* x, int max_it, double rtol, hipStream_t s);
 // x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)

@@ -26,6 +26,7 @@
 // place, left alone).
 #include "ctab.h"
 #include "kern_common.h"
+#include "kern_tile.h"
 
 namespace dgwm {
 
@@ -405,7 +406,9 @@ __global__ __launch_bounds__(kImThreads) void invmass_kernel(const InvMassArgs A
 // ---------------------------------------------------------------------------
 // Element-wise projection step (Sec. 4.2, eq. projectionspat):
 //   (M_e + D_e) x = M_e u_hat - scale g,   D_e(v, w) = (div v, tau_D,e div w)_e,
-// g = P p given.  Per cell, preconditioned CG with the cell's own M^{-1} as
+// g = P p given.  Enriched cells (their psi differs from cell to cell; cells
+// without enrichment take the direct per-layer solve): per cell,
+// preconditioned CG with the cell's own M^{-1} as
 // preconditioner; all vectors of the cell stay in LDS, the inner products
 // are fixed-order workgroup sums (every lane takes the same branch), and the
 // iteration stops when (r, M^{-1} r) has dropped below rtol^2 times its
@@ -650,6 +653,255 @@ __global__ __launch_bounds__(kPrjThreads) void projection_step_kernel(const Step
   if (ENR && tid < 3) S.x[eo + tid] = L.x[3 * NP3 + tid];
 }
 
+
+// Direct solve of the projection step in enriched cells (NP <= 5).  The
+// polynomial block of an enriched cell is the block of a cell without
+// enrichment of the same height (both Gauss rules integrate the polynomial
+// products exactly), P = |J| (Mh + tau Dh), solved with the layer's spectral
+// tables.  The enrichment unknowns are taken in the basis r e_d, r = psi - P psi
+// (P psi = sum_B a_B N_B, the L2 projection of the cached polynomial part),
+// which is mass-orthogonal to the polynomials: u = sum x'_B N_B + x_e r with
+// x_p = x'_p - a x_e.  In that basis (all entries divided by |J|, weights
+// without |J|)
+//   C'_d[c][B] = tau (d N_B / d x_c, d r / d x_d)_w,
+//   E'_cd = delta_cd (r, r)_w + tau (d r / d x_c, d r / d x_d)_w,
+//   b'_e,d = (r, r)_w u_e,d - (s/|J|) (g_e,d - sum_B a_B g_p[d][B]),
+// so the mass part of the Schur complement S' = E' - C'^T P^{-1} C' is the
+// exact (r, r) and nothing cancels as tau -> 0 (as for the inverse mass).
+// The four right-hand sides b_p, C'_0, C'_1, C'_2 of a cell take the first
+// spectral product together; every C'^T P^{-1} (.) is then a weighted dot
+// product of its outputs, sum_r y_j[r] y_k[r] / (1 + tau lambda_r); and by
+// linearity only x'_p = P^{-1} (b_p - C' x_e) takes the second product.  Four
+// cells per workgroup, one wavefront per cell in the dense products.  A cell
+// whose enrichment is off has x_e = 0 and x_p = P^{-1} b_p.
+struct BorderArgs {
+  InvMassArgs im;
+  const double* mats;   // K^{-1}, C^T, C^{-T}
+  const double* slots;  // per layer slot: Z, Z^T, lambda
+  const int32_t* map;
+  const double* tau_d;
+  const double* u_hat;
+  const double* g;
+  double scale;
+  double* x;
+  int tiles;            // tiles of four cells per enriched layer
+  int64_t ncol;         // cells per layer
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NP, int NQ, int NQY>
+__global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const BorderArgs S) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = 3 * NP3, NC = 16, LD = NC + 2, NPT = NQ * NQY * NQ;
+  constexpr int CPT = 4, RPT = (N + 63) / 64;
+  constexpr auto& tq = ct::tab<NP, NQ>;
+  constexpr auto& ty = ct::tab<NP, NQY>;
+  __shared__ double T[N * LD];
+  __shared__ double W0[9 * NPT], W1[9 * NPT], OUT[9 * NP3];
+  __shared__ double Mt[3 * NP2];
+  __shared__ double Av[NP3];
+  __shared__ double Er[4][6];  // per cell (d r/d x_c, d r/d x_d)_w: 00 01 02 11 12 22
+  __shared__ double XE[4][3];
+  __shared__ double red[6 * (kSpecThreads / 64)];
+  const InvMassArgs& A = S.im;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int slot = blockIdx.x / S.tiles;
+  const int64_t j0 = (int64_t)(blockIdx.x % S.tiles) * 4;
+  const int nc = S.ncol - j0 < 4 ? (int)(S.ncol - j0) : 4;
+  const int ey = slot == A.lower_slot ? 0 : A.ny - 1;
+  const double h[3] = {1.0 / A.ihx, 1.0 / A.ihy[ey], 1.0 / A.ihz};
+  const double detJ = h[0] * h[1] * h[2], f = S.scale / detJ;
+  // cell c of the tile: enriched index and cell index
+  auto enr_of = [&](int c) -> int64_t {
+    const int64_t j = j0 + c;
+    return j % A.nx + (int64_t)A.nx * (slot + (int64_t)A.nslots * (j / A.nx));
+  };
+  auto cell_of = [&](int c) -> int64_t {
+    const int64_t j = j0 + c;
+    return j % A.nx + (int64_t)A.nx * (ey + (int64_t)A.ny * (j / A.nx));
+  };
+  for (int i = tid; i < 3 * NP2; i += kSpecThreads) Mt[i] = S.mats[i];
+  // per cell (one at a time through W0/W1): grad r at the points, E' terms,
+  // and the coupling columns tau t'_d
+  for (int c = 0; c < 4; ++c) {
+    const bool valid = c < nc;
+    const int64_t b = valid ? enr_of(c) : 0;
+    const double tau = valid ? S.tau_d[cell_of(c)] : 0.0;
+    const double* ps = A.psi + b * A.psi_pts * 4;
+    for (int B = tid; B < NP3; B += kSpecThreads) Av[B] = valid ? A.apoly[b * apoly_stride(NP3) + B] : 0.0;
+    __syncthreads();
+    // reference gradient of P psi at the points: W0[d][q]
+    sweep_c<0, NP, NP, NP, NQ, false, false, MDt<NP, NQ>>(Av, NP3, W1, NPT, 1.0, 1, 0);
+    sweep_c<0, NP, NP, NP, NQ, false, false, MSt<NP, NQ>>(Av, NP3, W1 + NPT, NPT, 1.0, 1, 64);
+    __syncthreads();
+    sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(W1, NPT, W1 + 2 * NPT, NPT, 1.0, 1, 0);
+    sweep_c<1, NQ, NP, NP, NQY, false, false, MDt<NP, NQY>>(W1 + NPT, NPT, W1 + 3 * NPT, NPT, 1.0, 1, 64);
+    sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(W1 + NPT, NPT, W1 + 4 * NPT, NPT, 1.0, 1, 128);
+    __syncthreads();
+    sweep_c<2, NQ, NQY, NP, NQ, false, false, MSt<NP, NQ>>(W1 + 2 * NPT, NPT, W0, NPT, 1.0, 2, 0);
+    sweep_c<2, NQ, NQY, NP, NQ, false, false, MDt<NP, NQ>>(W1 + 4 * NPT, NPT, W0 + 2 * NPT, NPT, 1.0, 1, 128);
+    __syncthreads();
+    double e6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int q = tid; q < NPT; q += kSpecThreads) {
+      const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+      const double w = tq.w[qx] * ty.w[qy] * tq.w[qz];
+      double gr[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gr[d] = valid ? ps[q * 4 + 1 + d] - W0[d * NPT + q] / h[d] : 0.0;
+      e6[0] += w * gr[0] * gr[0];
+      e6[1] += w * gr[0] * gr[1];
+      e6[2] += w * gr[0] * gr[2];
+      e6[3] += w * gr[1] * gr[1];
+      e6[4] += w * gr[1] * gr[2];
+      e6[5] += w * gr[2] * gr[2];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) W1[(cc * 3 + d) * NPT + q] = w * gr[d] / h[cc];  // [component][d][q]
+    }
+    block_sum<6>(e6, red, tid);  // (its barriers also publish W1)
+    if (tid == 0)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) Er[c][i] = e6[i];
+    sweep_c<0, NQ, NQY, NQ, NP, true, false, MDt<NP, NQ>>(W1, NPT, W0, NPT, 1.0, 3, 0);
+    sweep_c<0, NQ, NQY, NQ, NP, true, false, MSt<NP, NQ>>(W1 + 3 * NPT, NPT, W0 + 3 * NPT, NPT, 1.0, 6, 64);
+    __syncthreads();
+    sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(W0, NPT, W1, NPT, 1.0, 3, 0);
+    sweep_c<1, NP, NQY, NQ, NP, true, false, MDt<NP, NQY>>(W0 + 3 * NPT, NPT, W1 + 3 * NPT, NPT, 1.0, 3, 64);
+    sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(W0 + 6 * NPT, NPT, W1 + 6 * NPT, NPT, 1.0, 3, 128);
+    __syncthreads();
+    sweep_c<2, NP, NP, NQ, NP, true, false, MSt<NP, NQ>>(W1, NPT, OUT, NP3, 1.0, 6, 0);
+    sweep_c<2, NP, NP, NQ, NP, true, false, MDt<NP, NQ>>(W1 + 6 * NPT, NPT, OUT + 6 * NP3, NP3, 1.0, 3, 128);
+    __syncthreads();
+    for (int it = tid; it < 3 * N; it += kSpecThreads) {
+      const int d = it / N, k = it - d * N, cc = k / NP3, B = k - cc * NP3;
+      T[k * LD + 4 * c + 1 + d] = tau * OUT[(cc * 3 + d) * NP3 + B];
+    }
+    for (int k = tid; k < N; k += kSpecThreads) T[k * LD + 4 * c] = valid ? -f * S.g[cell_of(c) * N + k] : 0.0;
+    __syncthreads();
+  }
+  // Mh^{-1} on all columns; column 0 becomes Mh^{-1} b_p = u_p + a u_e - f Mh^{-1} g_p
+  tile_sweep<NP, NC, 0>(T, Mt, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 1>(T, Mt, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 2>(T, Mt, tid);
+  __syncthreads();
+  for (int it = tid; it < 4 * N; it += kSpecThreads) {
+    const int c = it / N, k = it - c * N, cc = k / NP3, B = k - cc * NP3;
+    if (c >= nc) continue;
+    const int64_t b = enr_of(c);
+    const double a = A.apoly[b * apoly_stride(NP3) + B];
+    T[k * LD + 4 * c] += S.u_hat[cell_of(c) * N + k] + a * S.u_hat[A.ncell * N + 3 * b + cc];
+  }
+  __syncthreads();
+  tile_sweep<NP, NC, 0>(T, Mt + NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 1>(T, Mt + NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 2>(T, Mt + NP2, tid);
+  __syncthreads();
+  // wavefront wv owns cell wv: b'_e and the Schur complement
+  const bool valid = wv < nc;
+  const int64_t b = valid ? enr_of(wv) : 0;
+  const int64_t e = valid ? cell_of(wv) : 0;
+  const double tau = valid ? S.tau_d[e] : 0.0;
+  const double* ap = A.apoly + b * apoly_stride(NP3);
+  const bool on = valid && ap[NP3] != 0.0;
+  double ag[3] = {0.0, 0.0, 0.0};  // sum_B a_B g_p[d][B]
+  if (on) {
+    const double* gp = S.g + e * N;
+    for (int B = lane; B < NP3; B += 64) {
+      const double aB = ap[B];
+      ag[0] += aB * gp[B];
+      ag[1] += aB * gp[NP3 + B];
+      ag[2] += aB * gp[2 * NP3 + B];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ag[i] = wave_sum(ag[i]);
+  const int32_t lslot = S.map[ey];
+  const double* Zs = S.slots + (size_t)lslot * (2 * (size_t)N * N + N);
+  const double* lam = Zs + 2 * (size_t)N * N;
+  double acc[RPT][CPT];
+  tile_gemm<N, LD, RPT, CPT>(T, Zs, acc, lane, wv);
+  // weighted dot products G_jk = sum_r y_j[r] y_k[r] / (1 + tau lambda_r)
+  double G[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // 10 20 30 11 12 13 22 23 33
+  double sr[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = lane + 64 * i;
+    sr[i] = (i < RPT - 1 || r < N) ? 1.0 / (1.0 + tau * lam[r]) : 0.0;
+    const double y0 = acc[i][0], y1 = acc[i][1], y2 = acc[i][2], y3 = acc[i][3], w = sr[i];
+    G[0] += w * y1 * y0;
+    G[1] += w * y2 * y0;
+    G[2] += w * y3 * y0;
+    G[3] += w * y1 * y1;
+    G[4] += w * y1 * y2;
+    G[5] += w * y1 * y3;
+    G[6] += w * y2 * y2;
+    G[7] += w * y2 * y3;
+    G[8] += w * y3 * y3;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) G[i] = wave_sum(G[i]);
+  double xe[3] = {0.0, 0.0, 0.0};
+  if (on) {
+    const double rr = 1.0 / ap[NP3];
+    const double* ue = S.u_hat + A.ncell * N + 3 * b;
+    const double* ge = S.g + A.ncell * N + 3 * b;
+    const double* E = Er[wv];
+    // S' = E' - C'^T P^{-1} C' and rhs = b'_e - C'^T P^{-1} b_p (all divided by |J|)
+    const double s00 = rr + tau * E[0] - G[3], s01 = tau * E[1] - G[4], s02 = tau * E[2] - G[5];
+    const double s11 = rr + tau * E[3] - G[6], s12 = tau * E[4] - G[7], s22 = rr + tau * E[5] - G[8];
+    const double r0 = rr * ue[0] - f * (ge[0] - ag[0]) - G[0];
+    const double r1 = rr * ue[1] - f * (ge[1] - ag[1]) - G[1];
+    const double r2 = rr * ue[2] - f * (ge[2] - ag[2]) - G[2];
+    // symmetric 3 x 3 solve by cofactors
+    const double c00 = s11 * s22 - s12 * s12, c01 = s02 * s12 - s01 * s22, c02 = s01 * s12 - s02 * s11;
+    const double c11 = s00 * s22 - s02 * s02, c12 = s01 * s02 - s00 * s12, c22 = s00 * s11 - s01 * s01;
+    const double idet = 1.0 / (s00 * c00 + s01 * c01 + s02 * c02);
+    xe[0] = (c00 * r0 + c01 * r1 + c02 * r2) * idet;
+    xe[1] = (c01 * r0 + c11 * r1 + c12 * r2) * idet;
+    xe[2] = (c02 * r0 + c12 * r1 + c22 * r2) * idet;
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) XE[wv][d] = xe[d];
+  __syncthreads();  // every wavefront is done reading T; XE published
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = lane + 64 * i;
+    if (i < RPT - 1 || r < N)
+      T[r * LD + 4 * wv] = (acc[i][0] - xe[0] * acc[i][1] - xe[1] * acc[i][2] - xe[2] * acc[i][3]) * sr[i];
+  }
+  __syncthreads();
+  tile_gemm<N, LD, RPT, CPT>(T, Zs + (size_t)N * N, acc, lane, wv);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = lane + 64 * i;
+    if (i < RPT - 1 || r < N) T[r * LD + 4 * wv] = acc[i][0];
+  }
+  __syncthreads();
+  tile_sweep<NP, NC, 0>(T, Mt + 2 * NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 1>(T, Mt + 2 * NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 2>(T, Mt + 2 * NP2, tid);
+  __syncthreads();
+  // back to the psi basis: x_p = x'_p - a x_e
+  for (int it = tid; it < 4 * N; it += kSpecThreads) {
+    const int c = it / N, k = it - c * N, cc = k / NP3, B = k - cc * NP3;
+    if (c < nc)
+      S.x[cell_of(c) * N + k] = T[k * LD + 4 * c] - A.apoly[enr_of(c) * apoly_stride(NP3) + B] * XE[c][cc];
+  }
+  if (valid && lane < 3) S.x[A.ncell * N + 3 * b + lane] = XE[wv][lane];
+}
 }  // namespace
 
 #define DG_PRJ_COMBOS(X) X(3, 4, 8) X(3, 4, 4) X(4, 4, 8) X(4, 5, 8) X(4, 5, 5) X(5, 7, 8) X(6, 8, 8)
@@ -759,8 +1011,24 @@ int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_
   return set_error(DG_ERR_UNSUPPORTED, "inverse mass: degree not compiled");
 }
 
+namespace {
+template <int P, int Q, int W>
+int launch_enriched_step(const BorderArgs& B, const StepArgs& S, int64_t nenr, int grid, hipStream_t s) {
+  if constexpr (P <= 5)
+    hipLaunchKernelGGL((bordered_step_kernel<P, Q, W>), dim3((unsigned)grid), dim3(kSpecThreads), 0, s, B);
+  else  // the tile and the point fields exceed the LDS: per-cell CG
+    hipLaunchKernelGGL((projection_step_kernel<P, Q, W, true>), dim3((unsigned)nenr), dim3(kPrjThreads), 0, s, S, 0,
+                       0);
+  return check_hip(hipGetLastError(), "projection step kernel launch");
+}
+}  // namespace
+
 int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
                            double* x, int max_it, double rtol, hipStream_t s) {
+  int rc = ensure_spectral_tables(m, s);
+  // cells without enrichment: direct solve per layer
+  if (!rc) rc = launch_spectral_step(m, tau_d, u_hat, g, scale, x, s);
+  if (rc || m->nenr == 0) return rc;
   StepArgs S;
   S.im = invmass_args(m, nullptr, nullptr);
   S.tau_d = tau_d;
@@ -770,26 +1038,23 @@ int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* 
   S.rtol2 = rtol * rtol;
   S.max_it = max_it;
   S.x = x;
-  const int rc0 = ensure_psi_poly(m, S.im, s);
-  if (rc0) return rc0;
-  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
-  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
-  const int nl = hi - lo + 1;
-  const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
-  // regular cells need (k_u + 1, nq_u) only; enriched cells also the wall-normal rule
-#define X(p, q, w)                                                                                          \
-  if (m->np_u == p && m->P.nq_u == q && (m->nenr == 0 || m->P.nq_wn == w)) {                                \
-    if (nreg > 0) {                                                                                         \
-      hipLaunchKernelGGL((projection_step_kernel<p, q, q, false>), dim3((unsigned)nreg), dim3(kPrjThreads), 0, s, \
-                         S, lo, nl);                                                                        \
-      const int rc = check_hip(hipGetLastError(), "projection step kernel launch");                         \
-      if (rc) return rc;                                                                                    \
-    }                                                                                                       \
-    if (m->nenr > 0)                                                                                        \
-      hipLaunchKernelGGL((projection_step_kernel<p, q, w, true>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, \
-                         s, S, 0, 0);                                                                       \
-    return check_hip(hipGetLastError(), "projection step kernel launch");                                   \
-  }
+  rc = ensure_psi_poly(m, S.im, s);
+  if (rc) return rc;
+  BorderArgs B;
+  B.im = S.im;
+  spectral_pointers(m, &B.mats, &B.slots, &B.map);
+  B.tau_d = tau_d;
+  B.u_hat = u_hat;
+  B.g = g;
+  B.scale = scale;
+  B.x = x;
+  B.ncol = (int64_t)m->P.nx * m->P.nz;
+  const int64_t tiles = (B.ncol + 3) / 4;
+  if (tiles * m->n_enr_layers > INT32_MAX / 2) return set_error(DG_ERR_ARG, "projection step: mesh too large");
+  B.tiles = (int)tiles;
+  const int grid = (int)(tiles * m->n_enr_layers);
+#define X(p, q, w)                                                        \
+  if (m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) return launch_enriched_step<p, q, w>(B, S, m->nenr, grid, s);
   DG_PRJ_COMBOS(X)
 #undef X
   return set_error(DG_ERR_UNSUPPORTED, "projection step: (k_u+1, nq_u, nq_wn) combination not compiled");

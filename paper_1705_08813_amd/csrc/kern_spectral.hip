@@ -1,0 +1,353 @@
+// Direct solve of the element-wise projection step (arXiv 1705.08813, Sec.
+// 4.2, eq. projectionspat) in cells without enrichment, FP64.
+//
+// In a cell of height h_y (flat mesh, affine cell) the system is
+//   (M_e + D_e) x = M_e u_hat - s g,   M_e = |J| Mh,   D_e = |J| tau_D,e Dh,
+// with Mh the reference mass (the tensor product K (x) K (x) K of the 1-D
+// mass K of the velocity rule, per component) and Dh the div-div form with
+// physical derivatives and reference weights; Mh and Dh depend on the layer
+// only, tau_D,e on the cell.  With the Cholesky factor K = C C^T and
+// L = C (x) C (x) C (Mh = L L^T), and the eigendecomposition of the
+// whitened form  L^{-1} Dh L^{-T} = Z diag(lambda) Z^T  (once per distinct
+// layer height, on the host, by the cyclic Jacobi method),
+//   x = L^{-T} Z diag(1 / (1 + tau_D,e lambda)) Z^T L^T (u_hat - (s/|J|) Mh^{-1} g).
+// Mh^{-1}, L^T and L^{-T} are sweeps with 1-D matrices; Z^T and Z are dense
+// products shared by all cells of a layer, so a workgroup takes a tile of NC
+// cells of one layer and runs both products as a small GEMM out of LDS.  The
+// result is exact up to rounding: no iteration, every cell the same work.
+#include <algorithm>
+#include <thread>
+#include <vector>
+
+#include "kern_common.h"
+#include "kern_tile.h"
+#include "symeig.h"
+
+namespace dgwm {
+
+namespace {
+
+
+template <int NP>
+constexpr int spec_nc() {
+  return NP >= 6 ? 8 : 16;
+}
+
+struct SpecArgs {
+  int nx, ny, layer_lo, tiles, nblocks;  // tiles per layer; blocks in the launch
+  int64_t ncol;                          // cells per layer (nx * nz)
+  double hx, hz;
+  const double* hy;     // [ny] cell heights
+  const double* mats;   // [3][np][np]: K^{-1}, C^T, C^{-T} (row-major, out_a = sum_i M[a][i] in_i)
+  const double* slots;  // [slot][2 n^2 + n]: Z (row-major), Z^T (row-major), lambda
+  const int32_t* map;   // [ny] slot of each layer
+  const double* tau_d;
+  const double* u_hat;
+  const double* g;
+  double scale;
+  double* x;
+};
+
+template <int NP, int NC>
+__global__ __launch_bounds__(kSpecThreads) void spectral_step_kernel(const SpecArgs A) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = 3 * NP3, LD = NC + 2;
+  constexpr int CPT = NC / 4, RPT = (N + 63) / 64;
+  static_assert(NC % 4 == 0, "four cell groups");
+  __shared__ double T[N * LD];
+  __shared__ double Mt[3 * NP2];
+  __shared__ double tauc[NC];
+  // consecutive logical blocks (tiles of one layer) on one XCD: hardware
+  // block b runs on XCD b % 8
+  const int per = (A.nblocks + 7) / 8;
+  const int lb = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lb >= A.nblocks) return;
+  const int tid = threadIdx.x;
+  const int layer = A.layer_lo + lb / A.tiles;
+  const int64_t j0 = (int64_t)(lb % A.tiles) * NC;
+  const int nc = A.ncol - j0 < NC ? (int)(A.ncol - j0) : NC;
+  const int64_t rowc = (int64_t)A.nx * A.ny;
+  auto cell = [&](int c) -> int64_t {
+    const int64_t j = j0 + c;
+    return j % A.nx + (int64_t)A.nx * layer + rowc * (j / A.nx);
+  };
+  for (int i = tid; i < 3 * NP2; i += kSpecThreads) Mt[i] = A.mats[i];
+  if (tid < NC) tauc[tid] = tid < nc ? A.tau_d[cell(tid)] : 0.0;
+  const double detJ = A.hx * A.hy[layer] * A.hz;
+  for (int idx = tid; idx < NC * N; idx += kSpecThreads) {
+    const int c = idx / N, k = idx - c * N;
+    T[k * LD + c] = c < nc ? A.g[cell(c) * N + k] : 0.0;
+  }
+  __syncthreads();
+  // Mh^{-1} g
+  tile_sweep<NP, NC, 0>(T, Mt, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 1>(T, Mt, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 2>(T, Mt, tid);
+  __syncthreads();
+  const double f = A.scale / detJ;
+  for (int idx = tid; idx < NC * N; idx += kSpecThreads) {
+    const int c = idx / N, k = idx - c * N;
+    T[k * LD + c] = (c < nc ? A.u_hat[cell(c) * N + k] : 0.0) - f * T[k * LD + c];
+  }
+  __syncthreads();
+  // L^T (u_hat - f Mh^{-1} g)
+  tile_sweep<NP, NC, 0>(T, Mt + NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 1>(T, Mt + NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 2>(T, Mt + NP2, tid);
+  __syncthreads();
+  const double* Zs = A.slots + (size_t)A.map[layer] * (2 * (size_t)N * N + N);
+  const double* lam = Zs + 2 * (size_t)N * N;
+  const int rl = tid & 63, cg = tid >> 6;
+  double acc[RPT][CPT];
+  tile_gemm<N, LD, RPT, CPT>(T, Zs, acc, rl, cg);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = rl + 64 * i;
+    if (i < RPT - 1 || r < N) {
+      const double lr = lam[r];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) T[r * LD + cg * CPT + j] = acc[i][j] / (1.0 + tauc[cg * CPT + j] * lr);
+    }
+  }
+  __syncthreads();
+  tile_gemm<N, LD, RPT, CPT>(T, Zs + (size_t)N * N, acc, rl, cg);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = rl + 64 * i;
+    if (i < RPT - 1 || r < N) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) T[r * LD + cg * CPT + j] = acc[i][j];
+    }
+  }
+  __syncthreads();
+  // L^{-T}
+  tile_sweep<NP, NC, 0>(T, Mt + 2 * NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 1>(T, Mt + 2 * NP2, tid);
+  __syncthreads();
+  tile_sweep<NP, NC, 2>(T, Mt + 2 * NP2, tid);
+  __syncthreads();
+  for (int idx = tid; idx < NC * N; idx += kSpecThreads) {
+    const int c = idx / N, k = idx - c * N;
+    if (c < nc) A.x[cell(c) * N + k] = T[k * LD + c];
+  }
+}
+
+// Lower Cholesky factor of the symmetric positive definite n x n matrix a.
+void cholesky(int n, const std::vector<double>& a, std::vector<double>& c) {
+  c.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = a[j * n + j];
+    for (int k = 0; k < j; ++k) d -= c[j * n + k] * c[j * n + k];
+    c[j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double s = a[i * n + j];
+      for (int k = 0; k < j; ++k) s -= c[i * n + k] * c[j * n + k];
+      c[i * n + j] = s / c[j * n + j];
+    }
+  }
+}
+
+// Inverse of a lower triangular matrix (forward substitution per column).
+void lower_inverse(int n, const std::vector<double>& c, std::vector<double>& ci) {
+  ci.assign((size_t)n * n, 0.0);
+  for (int col = 0; col < n; ++col) {
+    for (int i = col; i < n; ++i) {
+      double s = i == col ? 1.0 : 0.0;
+      for (int k = col; k < i; ++k) s -= c[i * n + k] * ci[k * n + col];
+      ci[i * n + col] = s / c[i * n + i];
+    }
+  }
+}
+
+}  // namespace
+
+int spectral_layers(const dg_mesh& m, std::vector<int>* map, std::vector<double>* heights) {
+  const dg_mesh_params& P = m.P;
+  if (m.curved) return 0;
+  const int lo = 0, hi = P.ny - 1;  // every layer (enriched cells share their polynomial block)
+  std::vector<double> hs;
+  if (map) map->assign(P.ny, 0);
+  for (int j = lo; j <= hi; ++j) {
+    const double t0 = 2.0 * j / P.ny - 1.0, t1 = 2.0 * (j + 1) / P.ny - 1.0;
+    const double h = P.gamma > 0 ? std::tanh(P.gamma * t1) / std::tanh(P.gamma) - std::tanh(P.gamma * t0) / std::tanh(P.gamma)
+                                 : t1 - t0;
+    int s = -1;
+    for (size_t q = 0; q < hs.size(); ++q)
+      if (hs[q] == h) s = (int)q;
+    if (s < 0) {
+      s = (int)hs.size();
+      hs.push_back(h);
+    }
+    if (map) (*map)[j] = s;
+  }
+  if (heights) *heights = hs;
+  return (int)hs.size();
+}
+
+size_t spectral_table_doubles(const dg_mesh& m) {
+  const int ns = spectral_layers(m, nullptr, nullptr);
+  if (ns == 0) return 0;
+  const size_t n = 3 * (size_t)m.np_u * m.np_u * m.np_u;
+  return 3 * (size_t)m.np_u * m.np_u + (size_t)ns * (2 * n * n + n) + (m.P.ny + 1) / 2;  // + int32 map
+}
+
+// Host: 1-D factors, whitened div-div forms, their eigendecompositions; copies
+// everything into m->spec (synchronous on s).
+int ensure_spectral_tables(const dg_mesh* m, hipStream_t s) {
+  if (m->spec_ok) return DG_OK;
+  const dg_mesh_params& P = m->P;
+  const int np = m->np_u, nq = P.nq_u, np3 = np * np * np, n = 3 * np3, npt = nq * nq * nq;
+  std::vector<int> map;
+  std::vector<double> heights;
+  const int ns = spectral_layers(*m, &map, &heights);
+  if (ns == 0) return DG_OK;
+  const TabLayout Lu = tab_layout(np, nq, P.nq_wn);
+  std::vector<double> tu(Lu.size);
+  fill_tables(np, nq, P.nq_wn, tu.data());
+  const double* S = tu.data() + Lu.S;
+  const double* Sd = tu.data() + Lu.Sd;
+  const double* w = tu.data() + Lu.w;
+  std::vector<double> K((size_t)np * np), C, Ci;
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) {
+      double v = 0.0;
+      for (int q = 0; q < nq; ++q) v += w[q] * S[q * np + i] * S[q * np + j];
+      K[i * np + j] = v;
+    }
+  cholesky(np, K, C);
+  lower_inverse(np, C, Ci);
+  const size_t head = 3 * (size_t)np * np, per = 2 * (size_t)n * n + n;
+  std::vector<double> host(spectral_table_doubles(*m), 0.0);
+  double* Kinv = host.data();
+  double* CT = Kinv + np * np;
+  double* CiT = CT + np * np;
+  for (int a = 0; a < np; ++a)
+    for (int i = 0; i < np; ++i) {
+      double v = 0.0;  // K^{-1} = C^{-T} C^{-1}
+      for (int k = 0; k < np; ++k) v += Ci[k * np + a] * Ci[k * np + i];
+      Kinv[a * np + i] = v;
+      CT[a * np + i] = C[i * np + a];
+      CiT[a * np + i] = Ci[i * np + a];
+    }
+  // whitened 1-D tables: St = S C^{-T}, Sdt = Sd C^{-T}
+  std::vector<double> St((size_t)nq * np, 0.0), Sdt((size_t)nq * np, 0.0);
+  for (int q = 0; q < nq; ++q)
+    for (int a = 0; a < np; ++a)
+      for (int i = 0; i < np; ++i) {
+        St[q * np + a] += S[q * np + i] * Ci[a * np + i];
+        Sdt[q * np + a] += Sd[q * np + i] * Ci[a * np + i];
+      }
+  std::vector<int> sweeps(ns, 0);
+  auto work = [&](int slot) {
+    const double h[3] = {m->hx, heights[slot], m->hz};
+    // G[q][I] = sqrt(w_q) div of whitened basis function I at point q
+    std::vector<double> G((size_t)npt * n);
+    for (int qz = 0; qz < nq; ++qz)
+      for (int qy = 0; qy < nq; ++qy)
+        for (int qx = 0; qx < nq; ++qx) {
+          const int q = qx + nq * (qy + nq * qz);
+          const double sw = std::sqrt(w[qx] * w[qy] * w[qz]);
+          for (int iz = 0; iz < np; ++iz)
+            for (int iy = 0; iy < np; ++iy)
+              for (int ix = 0; ix < np; ++ix) {
+                const int B = ix + np * (iy + np * iz);
+                const double sx = St[qx * np + ix], sy = St[qy * np + iy], sz = St[qz * np + iz];
+                G[(size_t)q * n + B] = sw * Sdt[qx * np + ix] * sy * sz / h[0];
+                G[(size_t)q * n + np3 + B] = sw * sx * Sdt[qy * np + iy] * sz / h[1];
+                G[(size_t)q * n + 2 * np3 + B] = sw * sx * sy * Sdt[qz * np + iz] / h[2];
+              }
+        }
+    std::vector<double> Bm((size_t)n * n, 0.0), lam, vt;
+    for (int q = 0; q < npt; ++q) {
+      const double* gq = &G[(size_t)q * n];
+      for (int I = 0; I < n; ++I) {
+        const double gi = gq[I];
+        if (gi == 0.0) continue;
+        double* row = &Bm[(size_t)I * n];
+        for (int J = 0; J < n; ++J) row[J] += gi * gq[J];
+      }
+    }
+    sweeps[slot] = sym_eig_jacobi(n, Bm, lam, vt);
+    double* Z = host.data() + head + slot * per;
+    double* ZT = Z + (size_t)n * n;
+    double* L = ZT + (size_t)n * n;
+    for (int k = 0; k < n; ++k)
+      for (int r = 0; r < n; ++r) {
+        Z[(size_t)k * n + r] = vt[(size_t)r * n + k];  // Z[k][r]: entry k of eigenvector r
+        ZT[(size_t)k * n + r] = vt[(size_t)k * n + r];
+      }
+    for (int r = 0; r < n; ++r) L[r] = std::max(lam[r], 0.0);  // positive semidefinite form
+  };
+  const int nth = std::max(1, std::min<int>(ns, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&, t] {
+      for (int slot = t; slot < ns; slot += nth) work(slot);
+    });
+  for (auto& th : pool) th.join();
+  for (int slot = 0; slot < ns; ++slot)
+    if (sweeps[slot] < 0) return set_error(DG_ERR_NOT_CONVERGED, "projection step: eigendecomposition did not converge");
+  int32_t* mp = reinterpret_cast<int32_t*>(host.data() + head + ns * per);
+  for (int j = 0; j < P.ny; ++j) mp[j] = map[j];
+  int rc = check_hip(hipMemcpyAsync(m->spec, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, s),
+                     "copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "projection step tables");
+  if (!rc) m->spec_ok = 1;
+  return rc;
+}
+
+void spectral_pointers(const dg_mesh* m, const double** mats, const double** slots, const int32_t** map) {
+  const int np = m->np_u;
+  const size_t n = 3 * (size_t)np * np * np;
+  const int ns = spectral_layers(*m, nullptr, nullptr);
+  *mats = m->spec;
+  *slots = m->spec + 3 * np * np;
+  *map = reinterpret_cast<const int32_t*>(m->spec + 3 * np * np + (size_t)ns * (2 * n * n + n));
+}
+
+int launch_spectral_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
+                         double* x, hipStream_t s) {
+  const dg_mesh_params& P = m->P;
+  const int lo = (P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (P.fully_periodic || m->upper_slot < 0) ? P.ny - 1 : P.ny - 2;
+  const int nl = hi - lo + 1;
+  if (nl <= 0) return DG_OK;
+  const int np = m->np_u;
+  SpecArgs A;
+  A.nx = P.nx;
+  A.ny = P.ny;
+  A.layer_lo = lo;
+  A.ncol = (int64_t)P.nx * P.nz;
+  A.hx = m->hx;
+  A.hz = m->hz;
+  A.hy = m->hy;
+  spectral_pointers(m, &A.mats, &A.slots, &A.map);
+  A.tau_d = tau_d;
+  A.u_hat = u_hat;
+  A.g = g;
+  A.scale = scale;
+  A.x = x;
+#define X(p)                                                                                                \
+  if (np == p) {                                                                                            \
+    constexpr int nc = spec_nc<p>();                                                                        \
+    const int64_t tiles = (A.ncol + nc - 1) / nc;                                                           \
+    const int64_t nb = tiles * nl;                                                                          \
+    if (nb > INT32_MAX / 2) return set_error(DG_ERR_ARG, "projection step: mesh too large");                \
+    A.tiles = (int)tiles;                                                                                   \
+    A.nblocks = (int)nb;                                                                                    \
+    const int grid = ((A.nblocks + 7) / 8) * 8;                                                             \
+    hipLaunchKernelGGL((spectral_step_kernel<p, nc>), dim3((unsigned)grid), dim3(kSpecThreads), 0, s, A);   \
+    return check_hip(hipGetLastError(), "projection step kernel launch");                                   \
+  }
+  X(3) X(4) X(5) X(6)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "projection step: degree not compiled");
+}
+
+}  // namespace dgwm

@@ -113,3 +113,27 @@ def test_projection_step_rejects_bad_arguments():
     with pytest.raises(DgError) as ei:
         curved.projection_step(torch.ones(curved.n_cells, dtype=torch.float64, device="cuda"), uc, uc.clone(), 1.0)
     assert ei.value.code == -6
+
+
+def test_projection_step_without_penalty_is_inverse_mass():
+    """tau_D = 0 on the bench mesh: (M) x = M u_hat - s g, so x = u_hat - s M^{-1} g
+    in every cell (direct solve in regular cells, CG in enriched ones)."""
+    wl = PRESETS["large"]
+    cfg = wl.mesh
+    print("[gpu] projection step, zero penalty, large mesh", flush=True)
+    inp = draw_inputs(wl, want=("u", "tau"))
+    mesh = Mesh(cfg, 1600.0 * inp["tau"])
+    u = torch.tensor(inp["u"], device="cuda")
+    g = torch.tensor(np.random.default_rng(26).uniform(-1, 1, cfg.n_vel), device="cuda")
+    x = mesh.projection_step(torch.zeros(cfg.ncell, dtype=torch.float64, device="cuda"), u, g, 0.9)
+    ref = u - 0.9 * mesh.apply_inverse_mass(g)
+    n3 = 3 * (cfg.k_u + 1) ** 3
+    regular = np.ones(cfg.ncell, dtype=bool)
+    regular[O.enriched_cells(cfg)] = False
+    reg = torch.tensor(np.repeat(regular, n3), device="cuda")
+    err_reg = ((x[:cfg.ncell * n3][reg] - ref[:cfg.ncell * n3][reg]).abs().max() / ref.abs().max()).item()
+    err_all = ((x - ref).abs().max() / ref.abs().max()).item()
+    print(f"[gpu]   cells without enrichment {err_reg:.2e}, all {err_all:.2e}", flush=True)
+    # regular cells: exact solves; enriched cells: both sides carry the
+    # mass block's conditioning (up to ~1e7 here), bound 64 eps cond
+    assert err_reg <= 1e-12 and err_all <= 64 * EPS * 1e7
