@@ -51,8 +51,8 @@ struct SpecArgs {
 template <int NP, int NC>
 __global__ __launch_bounds__(kSpecThreads) void spectral_step_kernel(const SpecArgs A) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = 3 * NP3, LD = NC + 2;
-  constexpr int CPT = NC / 4, RPT = (N + 63) / 64;
-  static_assert(NC % 4 == 0, "four cell groups");
+  constexpr int WR = 2, CPW = NC / (4 / WR);       // wavefronts along rows; columns per wavefront
+  constexpr int RPW = ((N + 63) / 64 + WR - 1) / WR;  // row chunks per wavefront
   __shared__ double T[N * LD];
   __shared__ double Mt[3 * NP2];
   __shared__ double tauc[NC];
@@ -100,28 +100,29 @@ __global__ __launch_bounds__(kSpecThreads) void spectral_step_kernel(const SpecA
   __syncthreads();
   const double* Zs = A.slots + (size_t)A.map[layer] * (2 * (size_t)N * N + N);
   const double* lam = Zs + 2 * (size_t)N * N;
-  const int rl = tid & 63, cg = tid >> 6;
-  double acc[RPT][CPT];
-  tile_gemm<N, LD, RPT, CPT>(T, Zs, acc, rl, cg);
+  const int lane = tid & 63, wv = tid >> 6;
+  const int rw = wv % WR, c0 = (wv / WR) * CPW;
+  double acc[RPW][CPW];
+  tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs, acc, lane, wv);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = rl + 64 * i;
-    if (i < RPT - 1 || r < N) {
+  for (int i = 0; i < RPW; ++i) {
+    const int r = 64 * (rw + WR * i) + lane;
+    if (r < N) {
       const double lr = lam[r];
 #pragma unroll
-      for (int j = 0; j < CPT; ++j) T[r * LD + cg * CPT + j] = acc[i][j] / (1.0 + tauc[cg * CPT + j] * lr);
+      for (int j = 0; j < CPW; ++j) T[r * LD + c0 + j] = acc[i][j] / (1.0 + tauc[c0 + j] * lr);
     }
   }
   __syncthreads();
-  tile_gemm<N, LD, RPT, CPT>(T, Zs + (size_t)N * N, acc, rl, cg);
+  tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs + (size_t)N * N, acc, lane, wv);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = rl + 64 * i;
-    if (i < RPT - 1 || r < N) {
+  for (int i = 0; i < RPW; ++i) {
+    const int r = 64 * (rw + WR * i) + lane;
+    if (r < N) {
 #pragma unroll
-      for (int j = 0; j < CPT; ++j) T[r * LD + cg * CPT + j] = acc[i][j];
+      for (int j = 0; j < CPW; ++j) T[r * LD + c0 + j] = acc[i][j];
     }
   }
   __syncthreads();

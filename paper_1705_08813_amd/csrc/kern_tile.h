@@ -43,7 +43,7 @@ __device__ __forceinline__ void tile_gemm(const double* T, const double* __restr
   for (int i = 0; i < RPT; ++i)
 #pragma unroll
     for (int j = 0; j < CPT; ++j) acc[i][j] = 0.0;
-#pragma unroll 2
+#pragma unroll 8
   for (int k = 0; k < N; ++k) {
     double a[CPT];
 #pragma unroll
@@ -55,6 +55,39 @@ __device__ __forceinline__ void tile_gemm(const double* T, const double* __restr
         const double z = Z[(size_t)k * N + r];
 #pragma unroll
         for (int j = 0; j < CPT; ++j) acc[i][j] = fma(z, a[j], acc[i][j]);
+      }
+    }
+  }
+}
+
+// Split variant: wavefront wv takes row chunks rw + WR i (rw = wv % WR) and
+// the columns cw * CPW .. cw * CPW + CPW - 1 (cw = wv / WR), so each Z entry
+// is loaded by 4 / WR wavefronts and each tile value read by WR of them:
+// acc[i][j] = sum_k Z[k * N + r_i] T[k * LD + cw * CPW + j], r_i = 64 (rw + WR i) + lane.
+template <int N, int LD, int WR, int RPW, int CPW>
+__device__ __forceinline__ void tile_gemm_split(const double* T, const double* __restrict__ Z,
+                                                double (&acc)[RPW][CPW], int lane, int wv) {
+  const int rw = wv % WR, cw = wv / WR;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) acc[i][j] = 0.0;
+  int nrow = 0;  // chunks of this wavefront that hold rows
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+    if (64 * (rw + WR * i) < N) nrow = i + 1;
+#pragma unroll 8
+  for (int k = 0; k < N; ++k) {
+    double a[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) a[j] = T[k * LD + cw * CPW + j];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = 64 * (rw + WR * i) + lane;
+      if (i < nrow) {
+        const double z = r < N ? Z[(size_t)k * N + r] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) acc[i][j] = fma(z, a[j], acc[i][j]);
       }
     }
   }
