@@ -16,7 +16,7 @@ thread_local std::string g_err;
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 struct WsLayout {
-  size_t eta, hy, tab_u, tab_p, tau, tau_nodes, ws_part, psi, psi_prev, act, act_prev, minv, apoly, spec, diag, diag32, geo,
+  size_t eta, hy, tab_u, tab_p, tau, tau_nodes, ws_part, psi, psi_prev, act, act_prev, minv, apoly, coup, spec, diag, diag32, geo,
       meas, tauF, wdist;
   size_t mg_hy[kMaxLevels], mg_diag[kMaxLevels], mg_diag32[kMaxLevels];
   size_t cinv, cinv32, cscr;  // coarsest pseudo-inverse (FP64, FP32) and its assembly scratch
@@ -67,6 +67,7 @@ void keep_previous_space(dg_mesh* m) {
   std::swap(m->psi, m->psi_prev);
   std::swap(m->act, m->act_prev);
   m->apoly_ok = 0;
+  m->coup_ok = 0;
 }
 
 }  // namespace
@@ -161,6 +162,7 @@ WsLayout layout(const dg_mesh& m) {
   L.act_prev = o; o = up256(o + sizeof(int32_t) * (size_t)m.nenr);
   L.minv = o; o = up256(o + sizeof(double) * 2 * m.np_u * m.np_u);
   L.apoly = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (2 * m.np_u * m.np_u * m.np_u + 2));
+  L.coup = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (9 * m.np_u * m.np_u * m.np_u + 6));
   L.spec = o; o = up256(o + sizeof(double) * spectral_table_doubles(m));
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
   L.diag32 = o; o = up256(o + sizeof(float) * m.n_p);
@@ -253,6 +255,7 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
   m->minv = reinterpret_cast<double*>(base + W.minv);
   m->apoly = reinterpret_cast<double*>(base + W.apoly);
   m->spec = reinterpret_cast<double*>(base + W.spec);
+  m->coup = reinterpret_cast<double*>(base + W.coup);
   m->diag = reinterpret_cast<double*>(base + W.diag);
   m->diag32 = reinterpret_cast<float*>(base + W.diag32);
   for (int l = 0; l < m->mg_nlev; ++l) {

@@ -684,6 +684,7 @@ struct BorderArgs {
   const double* g;
   double scale;
   double* x;
+  const double* coup;   // [enr][coup_stride]: coupling columns and (grad r, grad r)_w
   int tiles;            // tiles of four cells per enriched layer
   int64_t ncol;         // cells per layer
 };
@@ -694,19 +695,85 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Per enriched cell, the psi-dependent parts of the bordered projection
+// step (they change only with psi; cached like the polynomial part):
+//   t'_d[c][B] = (d N_B / d x_c, d r / d x_d)_w  (3 x 3 NP^3, d-major), then
+//   (d r / d x_c, d r / d x_d)_w  for cd = 00 01 02 11 12 22,
+// with grad r = grad psi - grad P psi at the enriched volume points (weights
+// without |J|, physical derivatives).
+__host__ __device__ constexpr int coup_stride(int np3) { return 9 * np3 + 6; }
+
 template <int NP, int NQ, int NQY>
-__global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const BorderArgs S) {
-  constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = 3 * NP3, NC = 16, LD = NC + 2, NPT = NQ * NQY * NQ;
-  constexpr int CPT = 4, RPT = (N + 63) / 64;
+__global__ __launch_bounds__(kSpecThreads) void coupling_kernel(const InvMassArgs A, double* coup) {
+  constexpr int NP3 = NP * NP * NP, NPT = NQ * NQY * NQ;
   constexpr auto& tq = ct::tab<NP, NQ>;
   constexpr auto& ty = ct::tab<NP, NQY>;
-  __shared__ double T[N * LD];
   __shared__ double W0[9 * NPT], W1[9 * NPT], OUT[9 * NP3];
-  __shared__ double Mt[3 * NP2];
   __shared__ double Av[NP3];
-  __shared__ double Er[4][6];  // per cell (d r/d x_c, d r/d x_d)_w: 00 01 02 11 12 22
-  __shared__ double XE[4][3];
   __shared__ double red[6 * (kSpecThreads / 64)];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int64_t e = enriched_cell_index(A.nx, A.ny, A.lower_slot, A.nslots, b);
+  const int ey = (int)((e / A.nx) % A.ny);
+  const double h[3] = {1.0 / A.ihx, 1.0 / A.ihy[ey], 1.0 / A.ihz};
+  const double* ps = A.psi + b * A.psi_pts * 4;
+  for (int B = tid; B < NP3; B += kSpecThreads) Av[B] = A.apoly[b * apoly_stride(NP3) + B];
+  __syncthreads();
+  // reference gradient of P psi at the points: W0[d][q]
+  sweep_c<0, NP, NP, NP, NQ, false, false, MDt<NP, NQ>>(Av, NP3, W1, NPT, 1.0, 1, 0);
+  sweep_c<0, NP, NP, NP, NQ, false, false, MSt<NP, NQ>>(Av, NP3, W1 + NPT, NPT, 1.0, 1, 64);
+  __syncthreads();
+  sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(W1, NPT, W1 + 2 * NPT, NPT, 1.0, 1, 0);
+  sweep_c<1, NQ, NP, NP, NQY, false, false, MDt<NP, NQY>>(W1 + NPT, NPT, W1 + 3 * NPT, NPT, 1.0, 1, 64);
+  sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(W1 + NPT, NPT, W1 + 4 * NPT, NPT, 1.0, 1, 128);
+  __syncthreads();
+  sweep_c<2, NQ, NQY, NP, NQ, false, false, MSt<NP, NQ>>(W1 + 2 * NPT, NPT, W0, NPT, 1.0, 2, 0);
+  sweep_c<2, NQ, NQY, NP, NQ, false, false, MDt<NP, NQ>>(W1 + 4 * NPT, NPT, W0 + 2 * NPT, NPT, 1.0, 1, 128);
+  __syncthreads();
+  double e6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int q = tid; q < NPT; q += kSpecThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+    const double w = tq.w[qx] * ty.w[qy] * tq.w[qz];
+    double gr[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gr[d] = ps[q * 4 + 1 + d] - W0[d * NPT + q] / h[d];
+    e6[0] += w * gr[0] * gr[0];
+    e6[1] += w * gr[0] * gr[1];
+    e6[2] += w * gr[0] * gr[2];
+    e6[3] += w * gr[1] * gr[1];
+    e6[4] += w * gr[1] * gr[2];
+    e6[5] += w * gr[2] * gr[2];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) W1[(cc * 3 + d) * NPT + q] = w * gr[d] / h[cc];  // [component][d][q]
+  }
+  block_sum<6>(e6, red, tid);  // (its barriers also publish W1)
+  double* out = coup + b * coup_stride(NP3);
+  if (tid < 6) out[9 * NP3 + tid] = e6[tid];
+  sweep_c<0, NQ, NQY, NQ, NP, true, false, MDt<NP, NQ>>(W1, NPT, W0, NPT, 1.0, 3, 0);
+  sweep_c<0, NQ, NQY, NQ, NP, true, false, MSt<NP, NQ>>(W1 + 3 * NPT, NPT, W0 + 3 * NPT, NPT, 1.0, 6, 64);
+  __syncthreads();
+  sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(W0, NPT, W1, NPT, 1.0, 3, 0);
+  sweep_c<1, NP, NQY, NQ, NP, true, false, MDt<NP, NQY>>(W0 + 3 * NPT, NPT, W1 + 3 * NPT, NPT, 1.0, 3, 64);
+  sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(W0 + 6 * NPT, NPT, W1 + 6 * NPT, NPT, 1.0, 3, 128);
+  __syncthreads();
+  sweep_c<2, NP, NP, NQ, NP, true, false, MSt<NP, NQ>>(W1, NPT, OUT, NP3, 1.0, 6, 0);
+  sweep_c<2, NP, NP, NQ, NP, true, false, MDt<NP, NQ>>(W1 + 6 * NPT, NPT, OUT + 6 * NP3, NP3, 1.0, 3, 128);
+  __syncthreads();
+  for (int it = tid; it < 9 * NP3; it += kSpecThreads) {
+    const int d = it / (3 * NP3), k = it - d * 3 * NP3, cc = k / NP3, B = k - cc * NP3;
+    out[it] = OUT[(cc * 3 + d) * NP3 + B];
+  }
+}
+
+template <int NP, int NQ, int NQY>
+__global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const BorderArgs S) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = 3 * NP3, NC = 16, LD = NC + 2;
+  constexpr int CPT = 4, RPT = (N + 63) / 64;
+  __shared__ double T[N * LD];
+  __shared__ double Mt[3 * NP2];
+  __shared__ double XE[4][3];
   const InvMassArgs& A = S.im;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int slot = blockIdx.x / S.tiles;
@@ -725,65 +792,19 @@ __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const Borde
     return j % A.nx + (int64_t)A.nx * (ey + (int64_t)A.ny * (j / A.nx));
   };
   for (int i = tid; i < 3 * NP2; i += kSpecThreads) Mt[i] = S.mats[i];
-  // per cell (one at a time through W0/W1): grad r at the points, E' terms,
-  // and the coupling columns tau t'_d
-  for (int c = 0; c < 4; ++c) {
-    const bool valid = c < nc;
-    const int64_t b = valid ? enr_of(c) : 0;
-    const double tau = valid ? S.tau_d[cell_of(c)] : 0.0;
-    const double* ps = A.psi + b * A.psi_pts * 4;
-    for (int B = tid; B < NP3; B += kSpecThreads) Av[B] = valid ? A.apoly[b * apoly_stride(NP3) + B] : 0.0;
-    __syncthreads();
-    // reference gradient of P psi at the points: W0[d][q]
-    sweep_c<0, NP, NP, NP, NQ, false, false, MDt<NP, NQ>>(Av, NP3, W1, NPT, 1.0, 1, 0);
-    sweep_c<0, NP, NP, NP, NQ, false, false, MSt<NP, NQ>>(Av, NP3, W1 + NPT, NPT, 1.0, 1, 64);
-    __syncthreads();
-    sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(W1, NPT, W1 + 2 * NPT, NPT, 1.0, 1, 0);
-    sweep_c<1, NQ, NP, NP, NQY, false, false, MDt<NP, NQY>>(W1 + NPT, NPT, W1 + 3 * NPT, NPT, 1.0, 1, 64);
-    sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(W1 + NPT, NPT, W1 + 4 * NPT, NPT, 1.0, 1, 128);
-    __syncthreads();
-    sweep_c<2, NQ, NQY, NP, NQ, false, false, MSt<NP, NQ>>(W1 + 2 * NPT, NPT, W0, NPT, 1.0, 2, 0);
-    sweep_c<2, NQ, NQY, NP, NQ, false, false, MDt<NP, NQ>>(W1 + 4 * NPT, NPT, W0 + 2 * NPT, NPT, 1.0, 1, 128);
-    __syncthreads();
-    double e6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int q = tid; q < NPT; q += kSpecThreads) {
-      const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
-      const double w = tq.w[qx] * ty.w[qy] * tq.w[qz];
-      double gr[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) gr[d] = valid ? ps[q * 4 + 1 + d] - W0[d * NPT + q] / h[d] : 0.0;
-      e6[0] += w * gr[0] * gr[0];
-      e6[1] += w * gr[0] * gr[1];
-      e6[2] += w * gr[0] * gr[2];
-      e6[3] += w * gr[1] * gr[1];
-      e6[4] += w * gr[1] * gr[2];
-      e6[5] += w * gr[2] * gr[2];
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) W1[(cc * 3 + d) * NPT + q] = w * gr[d] / h[cc];  // [component][d][q]
+  // columns: -f g_p, then tau t'_d (zero in padding cells)
+  for (int it = tid; it < 4 * 4 * N; it += kSpecThreads) {
+    const int c = it / (4 * N), r = it - c * 4 * N, col = r / N, k = r - col * N;
+    double v = 0.0;
+    if (c < nc) {
+      if (col == 0)
+        v = -f * S.g[cell_of(c) * N + k];
+      else
+        v = S.tau_d[cell_of(c)] * S.coup[enr_of(c) * coup_stride(NP3) + (col - 1) * N + k];
     }
-    block_sum<6>(e6, red, tid);  // (its barriers also publish W1)
-    if (tid == 0)
-#pragma unroll
-      for (int i = 0; i < 6; ++i) Er[c][i] = e6[i];
-    sweep_c<0, NQ, NQY, NQ, NP, true, false, MDt<NP, NQ>>(W1, NPT, W0, NPT, 1.0, 3, 0);
-    sweep_c<0, NQ, NQY, NQ, NP, true, false, MSt<NP, NQ>>(W1 + 3 * NPT, NPT, W0 + 3 * NPT, NPT, 1.0, 6, 64);
-    __syncthreads();
-    sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(W0, NPT, W1, NPT, 1.0, 3, 0);
-    sweep_c<1, NP, NQY, NQ, NP, true, false, MDt<NP, NQY>>(W0 + 3 * NPT, NPT, W1 + 3 * NPT, NPT, 1.0, 3, 64);
-    sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(W0 + 6 * NPT, NPT, W1 + 6 * NPT, NPT, 1.0, 3, 128);
-    __syncthreads();
-    sweep_c<2, NP, NP, NQ, NP, true, false, MSt<NP, NQ>>(W1, NPT, OUT, NP3, 1.0, 6, 0);
-    sweep_c<2, NP, NP, NQ, NP, true, false, MDt<NP, NQ>>(W1 + 6 * NPT, NPT, OUT + 6 * NP3, NP3, 1.0, 3, 128);
-    __syncthreads();
-    for (int it = tid; it < 3 * N; it += kSpecThreads) {
-      const int d = it / N, k = it - d * N, cc = k / NP3, B = k - cc * NP3;
-      T[k * LD + 4 * c + 1 + d] = tau * OUT[(cc * 3 + d) * NP3 + B];
-    }
-    for (int k = tid; k < N; k += kSpecThreads) T[k * LD + 4 * c] = valid ? -f * S.g[cell_of(c) * N + k] : 0.0;
-    __syncthreads();
+    T[k * LD + 4 * c + col] = v;
   }
+  __syncthreads();
   // Mh^{-1} on all columns; column 0 becomes Mh^{-1} b_p = u_p + a u_e - f Mh^{-1} g_p
   tile_sweep<NP, NC, 0>(T, Mt, tid);
   __syncthreads();
@@ -854,7 +875,7 @@ __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const Borde
     const double rr = 1.0 / ap[NP3];
     const double* ue = S.u_hat + A.ncell * N + 3 * b;
     const double* ge = S.g + A.ncell * N + 3 * b;
-    const double* E = Er[wv];
+    const double* E = S.coup + b * coup_stride(NP3) + 9 * NP3;
     // S' = E' - C'^T P^{-1} C' and rhs = b'_e - C'^T P^{-1} b_p (all divided by |J|)
     const double s00 = rr + tau * E[0] - G[3], s01 = tau * E[1] - G[4], s02 = tau * E[2] - G[5];
     const double s11 = rr + tau * E[3] - G[6], s12 = tau * E[4] - G[7], s22 = rr + tau * E[5] - G[8];
@@ -1040,7 +1061,24 @@ int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* 
   S.x = x;
   rc = ensure_psi_poly(m, S.im, s);
   if (rc) return rc;
+  if (m->np_u <= 5 && !m->coup_ok) {
+    bool launched = false;
+#define X(p, q, w)                                                                                               \
+    if (!launched && m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                        \
+      if constexpr (p <= 5)                                                                                      \
+        hipLaunchKernelGGL((coupling_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kSpecThreads), 0, s, S.im, \
+                           m->coup);                                                                             \
+      launched = true;                                                                                           \
+    }
+    DG_PRJ_COMBOS(X)
+#undef X
+    if (!launched) return set_error(DG_ERR_UNSUPPORTED, "projection step: (k_u+1, nq_u, nq_wn) combination not compiled");
+    rc = check_hip(hipGetLastError(), "projection step coupling kernel launch");
+    if (rc) return rc;
+    m->coup_ok = 1;
+  }
   BorderArgs B;
+  B.coup = m->coup;
   B.im = S.im;
   spectral_pointers(m, &B.mats, &B.slots, &B.map);
   B.tau_d = tau_d;

@@ -137,3 +137,24 @@ def test_projection_step_without_penalty_is_inverse_mass():
     # regular cells: exact solves; enriched cells: both sides carry the
     # mass block's conditioning (up to ~1e7 here), bound 64 eps cond
     assert err_reg <= 1e-12 and err_all <= 64 * EPS * 1e7
+
+
+def test_projection_step_follows_wall_shear_update():
+    """The cached psi-dependent parts are refreshed by a wall-shear update:
+    step, update to a new tau_w, step again -> the oracle on the new psi."""
+    cfg = CASES["k3"]
+    print("[gpu] projection step after a wall-shear update", flush=True)
+    inp = draw_inputs(Workload("ps", cfg, 27, 0.5, 1.5))
+    tau2 = 3.0 * inp["tau"]
+    g = np.random.default_rng(28).uniform(-1, 1, cfg.n_vel)
+    tau_d = O.divdiv_tau(cfg, inp["u"], 0.05, tau=tau2)
+    mesh = Mesh(cfg, inp["tau"])
+    td, u, gd = (torch.tensor(a, device="cuda") for a in (tau_d, inp["u"], g))
+    mesh.projection_step(td, u, gd, 0.7)
+    mesh.update_wall_shear(torch.tensor(tau2, device="cuda"))
+    x = mesh.projection_step(td, u, gd, 0.7).cpu().numpy()
+    cells = O.enriched_cells(cfg)
+    psi4 = O.psi_volume4(cfg, cells, tau=tau2)
+    ref = OP.projection_step(cfg, inp["u"], g, 0.7, tau_d, psi4)
+    _, conds = OP.inverse_mass(cfg, inp["u"], psi4[..., 0], return_cond=True)
+    _check(cfg, x, ref, conds, range(cfg.ncell))
