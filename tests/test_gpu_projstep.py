@@ -26,6 +26,7 @@ CASES = {
     "k5": MeshConfig(nx=2, ny=3, nz=2, gamma=0.8, k_u=5, k_p=4, nq_u=8, nq_p=5, nq_wn=8, nu=1.0 / 600),
     "k3_one_sided": MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=3, k_p=2, nq_u=5, nq_p=3, nq_wn=8, nu=1.0 / 400,
                                enrich_upper=0),
+    "k3_two_layers": MeshConfig(nx=3, ny=2, nz=2, gamma=1.0, k_u=3, k_p=2, nq_u=5, nq_p=3, nq_wn=8, nu=1.0 / 400),
     "k3_plain": MeshConfig(nx=3, ny=3, nz=2, gamma=1.1, k_u=3, k_p=2, nq_u=5, nq_p=3, enrich_lower=0,
                            enrich_upper=0),
     "k2_periodic": MeshConfig(nx=3, ny=3, nz=2, k_u=2, k_p=1, nq_u=4, nq_p=2, fully_periodic=1),
@@ -158,3 +159,16 @@ def test_projection_step_follows_wall_shear_update():
     ref = OP.projection_step(cfg, inp["u"], g, 0.7, tau_d, psi4)
     _, conds = OP.inverse_mass(cfg, inp["u"], psi4[..., 0], return_cond=True)
     _check(cfg, x, ref, conds, range(cfg.ncell))
+
+
+def test_projection_step_is_repeatable():
+    """Two calls on the same inputs give the same bits (fixed-order sums, no atomics)."""
+    cfg = CASES["k4"]
+    inp = draw_inputs(Workload("ps", cfg, 29, 0.5, 1.5))
+    mesh = Mesh(cfg, inp["tau"])
+    td = torch.tensor(O.divdiv_tau(cfg, inp["u"], 0.05, tau=inp["tau"]), device="cuda")
+    u = torch.tensor(inp["u"], device="cuda")
+    g = torch.tensor(np.random.default_rng(30).uniform(-1, 1, cfg.n_vel), device="cuda")
+    x1 = mesh.projection_step(td, u, g, 0.7)
+    x2 = mesh.projection_step(td, u, g, 0.7)
+    assert torch.equal(x1, x2)
