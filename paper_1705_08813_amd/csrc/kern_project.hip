@@ -770,7 +770,6 @@ __global__ __launch_bounds__(kSpecThreads) void coupling_kernel(const InvMassArg
 template <int NP, int NQ, int NQY>
 __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const BorderArgs S) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = 3 * NP3, NC = 16, LD = NC + 2;
-  constexpr int CPT = 4, RPT = (N + 63) / 64;
   __shared__ double T[N * LD];
   __shared__ double Mt[3 * NP2];
   __shared__ double XE[4][3];
@@ -826,7 +825,8 @@ __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const Borde
   __syncthreads();
   tile_sweep<NP, NC, 2>(T, Mt + NP2, tid);
   __syncthreads();
-  // wavefront wv owns cell wv: b'_e and the Schur complement
+  // per-cell scalars: wavefront wv <-> cell wv
+  __shared__ double TAU[4], Gp[2][4][9];
   const bool valid = wv < nc;
   const int64_t b = valid ? enr_of(wv) : 0;
   const int64_t e = valid ? cell_of(wv) : 0;
@@ -845,31 +845,57 @@ __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const Borde
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) ag[i] = wave_sum(ag[i]);
+  if (lane == 0) TAU[wv] = tau;
   const int32_t lslot = S.map[ey];
   const double* Zs = S.slots + (size_t)lslot * (2 * (size_t)N * N + N);
   const double* lam = Zs + 2 * (size_t)N * N;
-  double acc[RPT][CPT];
-  tile_gemm<N, LD, RPT, CPT>(T, Zs, acc, lane, wv);
-  // weighted dot products G_jk = sum_r y_j[r] y_k[r] / (1 + tau lambda_r)
-  double G[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // 10 20 30 11 12 13 22 23 33
-  double sr[RPT];
+  __syncthreads();
+  // dense products split 2 x 2: wavefront (rw, cw) takes row chunks rw + 2 i
+  // and the columns of cells 2 cw, 2 cw + 1
+  constexpr int WR = 2, CPW = 8, RPW = ((N + 63) / 64 + WR - 1) / WR;
+  const int rw = wv % WR, cw = wv / WR;
+  double acc[RPW][CPW];
+  tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs, acc, lane, wv);
+  // weighted dot products G_jk = sum_r y_j[r] y_k[r] / (1 + tau lambda_r), partial over this row half
+  double sr[RPW][2];
+  double Gl[2][9];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = lane + 64 * i;
-    sr[i] = (i < RPT - 1 || r < N) ? 1.0 / (1.0 + tau * lam[r]) : 0.0;
-    const double y0 = acc[i][0], y1 = acc[i][1], y2 = acc[i][2], y3 = acc[i][3], w = sr[i];
-    G[0] += w * y1 * y0;
-    G[1] += w * y2 * y0;
-    G[2] += w * y3 * y0;
-    G[3] += w * y1 * y1;
-    G[4] += w * y1 * y2;
-    G[5] += w * y1 * y3;
-    G[6] += w * y2 * y2;
-    G[7] += w * y2 * y3;
-    G[8] += w * y3 * y3;
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Gl[m][k] = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = 64 * (rw + WR * i) + lane;
+    const double lr = r < N ? lam[r] : 0.0;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double w = r < N ? 1.0 / (1.0 + TAU[2 * cw + m] * lr) : 0.0;
+      sr[i][m] = w;
+      const double y0 = acc[i][4 * m], y1 = acc[i][4 * m + 1], y2 = acc[i][4 * m + 2], y3 = acc[i][4 * m + 3];
+      Gl[m][0] += w * y1 * y0;  // 10 20 30 11 12 13 22 23 33
+      Gl[m][1] += w * y2 * y0;
+      Gl[m][2] += w * y3 * y0;
+      Gl[m][3] += w * y1 * y1;
+      Gl[m][4] += w * y1 * y2;
+      Gl[m][5] += w * y1 * y3;
+      Gl[m][6] += w * y2 * y2;
+      Gl[m][7] += w * y2 * y3;
+      Gl[m][8] += w * y3 * y3;
+    }
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) G[i] = wave_sum(G[i]);
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Gl[m][k] = wave_sum(Gl[m][k]);
+  if (lane == 0)
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Gp[rw][2 * cw + m][k] = Gl[m][k];
+  __syncthreads();  // every wavefront is done reading T; partial sums published
+  double G[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) G[k] = Gp[0][wv][k] + Gp[1][wv][k];
   double xe[3] = {0.0, 0.0, 0.0};
   if (on) {
     const double rr = 1.0 / ap[NP3];
@@ -893,20 +919,27 @@ __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const Borde
   if (lane == 0)
 #pragma unroll
     for (int d = 0; d < 3; ++d) XE[wv][d] = xe[d];
-  __syncthreads();  // every wavefront is done reading T; XE published
+  __syncthreads();  // XE published
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = lane + 64 * i;
-    if (i < RPT - 1 || r < N)
-      T[r * LD + 4 * wv] = (acc[i][0] - xe[0] * acc[i][1] - xe[1] * acc[i][2] - xe[2] * acc[i][3]) * sr[i];
+  for (int i = 0; i < RPW; ++i) {
+    const int r = 64 * (rw + WR * i) + lane;
+    if (r < N)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int cl = 2 * cw + m;
+        T[r * LD + 4 * cl] = (acc[i][4 * m] - XE[cl][0] * acc[i][4 * m + 1] - XE[cl][1] * acc[i][4 * m + 2] -
+                              XE[cl][2] * acc[i][4 * m + 3]) * sr[i][m];
+      }
   }
   __syncthreads();
-  tile_gemm<N, LD, RPT, CPT>(T, Zs + (size_t)N * N, acc, lane, wv);
+  tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs + (size_t)N * N, acc, lane, wv);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = lane + 64 * i;
-    if (i < RPT - 1 || r < N) T[r * LD + 4 * wv] = acc[i][0];
+  for (int i = 0; i < RPW; ++i) {
+    const int r = 64 * (rw + WR * i) + lane;
+    if (r < N)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) T[r * LD + 4 * (2 * cw + m)] = acc[i][4 * m];
   }
   __syncthreads();
   tile_sweep<NP, NC, 0>(T, Mt + 2 * NP2, tid);
