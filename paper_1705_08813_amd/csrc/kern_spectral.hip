@@ -101,29 +101,55 @@ __global__ __launch_bounds__(kSpecThreads) void spectral_step_kernel(const SpecA
   const double* Zs = A.slots + (size_t)A.map[layer] * (2 * (size_t)N * N + N);
   const double* lam = Zs + 2 * (size_t)N * N;
   const int lane = tid & 63, wv = tid >> 6;
-  const int rw = wv % WR, c0 = (wv / WR) * CPW;
-  double acc[RPW][CPW];
-  tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs, acc, lane, wv);
-  __syncthreads();
+  if constexpr (NC == 16) {
+    // matrix cores: wavefront wv owns row tiles wv + 4 q, all 16 columns
+    constexpr int RTW = ((N + 15) / 16 + 3) / 4;
+    dgwm_d4 acc[RTW];
+    tile_gemm_mfma<N, LD, RTW>(T, Zs, acc, lane, wv);
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int r = 64 * (rw + WR * i) + lane;
-    if (r < N) {
-      const double lr = lam[r];
+    for (int q = 0; q < RTW; ++q)
 #pragma unroll
-      for (int j = 0; j < CPW; ++j) T[r * LD + c0 + j] = acc[i][j] / (1.0 + tauc[c0 + j] * lr);
+      for (int j = 0; j < 4; ++j) {
+        const int r = 16 * (wv + 4 * q) + 4 * j + (lane >> 4), c = lane & 15;
+        if (r < N) T[r * LD + c] = acc[q][j] / (1.0 + tauc[c] * lam[r]);
+      }
+    __syncthreads();
+    tile_gemm_mfma<N, LD, RTW>(T, Zs + (size_t)N * N, acc, lane, wv);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RTW; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = 16 * (wv + 4 * q) + 4 * j + (lane >> 4), c = lane & 15;
+        if (r < N) T[r * LD + c] = acc[q][j];
+      }
+  } else {
+    const int rw = wv % WR, c0 = (wv / WR) * CPW;
+    double acc[RPW][CPW];
+    tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs, acc, lane, wv);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = 64 * (rw + WR * i) + lane;
+      if (r < N) {
+        const double lr = lam[r];
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) T[r * LD + c0 + j] = acc[i][j] / (1.0 + tauc[c0 + j] * lr);
+      }
     }
-  }
-  __syncthreads();
-  tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs + (size_t)N * N, acc, lane, wv);
-  __syncthreads();
+    __syncthreads();
+    tile_gemm_split<N, LD, WR, RPW, CPW>(T, Zs + (size_t)N * N, acc, lane, wv);
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int r = 64 * (rw + WR * i) + lane;
-    if (r < N) {
+    for (int i = 0; i < RPW; ++i) {
+      const int r = 64 * (rw + WR * i) + lane;
+      if (r < N) {
 #pragma unroll
-      for (int j = 0; j < CPW; ++j) T[r * LD + c0 + j] = acc[i][j];
+        for (int j = 0; j < CPW; ++j) T[r * LD + c0 + j] = acc[i][j];
+      }
     }
+    __syncthreads();
   }
   __syncthreads();
   // L^{-T}

@@ -93,4 +93,51 @@ __device__ __forceinline__ void tile_gemm_split(const double* T, const double* _
   }
 }
 
+typedef double dgwm_d4 __attribute__((ext_vector_type(4)));
+
+// Matrix-core variant for 16-column tiles (FP64 MFMA 16 x 16 x 4): row tile
+// t = wv + 4 q of wavefront wv is D = Z^T(rows 16 t .. 16 t + 15) T.  Operand
+// lanes: A (Z entries) lane l holds row l % 16, k = k0 + l / 16; B (tile)
+// lane l holds k = k0 + l / 16, column l % 16; result element j of lane l is
+// row 16 t + 4 j + l / 16, column l % 16.  Rows and k beyond N read zero.
+// The operands of the k-steps two ahead are loaded before the current
+// step's products are issued.
+template <int N, int LD, int RTW>
+__device__ __forceinline__ void tile_gemm_mfma(const double* T, const double* __restrict__ Z, dgwm_d4 (&acc)[RTW],
+                                               int lane, int wv) {
+  constexpr int NT = (N + 15) / 16, NK = (N + 3) / 4;  // row tiles; k-steps
+  constexpr int PF = 8;                                 // prefetch depth (k-steps)
+#pragma unroll
+  for (int q = 0; q < RTW; ++q) acc[q] = dgwm_d4{0.0, 0.0, 0.0, 0.0};
+  const int lk = lane >> 4, lr = lane & 15;
+  double fa[PF][RTW], fb[PF];
+  auto load = [&](int step, double (&a)[RTW], double& b) {
+    const int kk = 4 * step + lk;
+    const bool kin = step < NK && kk < N;
+    b = kin ? T[kk * LD + lr] : 0.0;
+#pragma unroll
+    for (int q = 0; q < RTW; ++q) {
+      const int r = 16 * (wv + 4 * q) + lr;
+      a[q] = (kin && r < N) ? Z[(size_t)kk * N + r] : 0.0;
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < PF; ++p) load(p, fa[p], fb[p]);
+  for (int s0 = 0; s0 < NK; s0 += PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      double a[RTW], b = fb[p];
+#pragma unroll
+      for (int q = 0; q < RTW; ++q) a[q] = fa[p][q];
+      load(s0 + p + PF, fa[p], fb[p]);
+      if (s0 + p < NK) {  // uniform
+#pragma unroll
+        for (int q = 0; q < RTW; ++q)
+          if (wv + 4 * q < NT)  // uniform over the wavefront
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b, acc[q], 0, 0, 0);
+      }
+    }
+  }
+}
+
 }  // namespace dgwm
