@@ -406,9 +406,10 @@ __global__ __launch_bounds__(kImThreads) void invmass_kernel(const InvMassArgs A
 // ---------------------------------------------------------------------------
 // Element-wise projection step (Sec. 4.2, eq. projectionspat):
 //   (M_e + D_e) x = M_e u_hat - scale g,   D_e(v, w) = (div v, tau_D,e div w)_e,
-// g = P p given.  Enriched cells (their psi differs from cell to cell; cells
-// without enrichment take the direct per-layer solve): per cell,
-// preconditioned CG with the cell's own M^{-1} as
+// g = P p given.  This iterative form serves the enriched cells at k = 5,
+// whose tile and point fields exceed the LDS of the direct bordered solve
+// below (cells without enrichment always take the direct per-layer solve):
+// per cell, preconditioned CG with the cell's own M^{-1} as
 // preconditioner; all vectors of the cell stay in LDS, the inner products
 // are fixed-order workgroup sums (every lane takes the same branch), and the
 // iteration stops when (r, M^{-1} r) has dropped below rtol^2 times its

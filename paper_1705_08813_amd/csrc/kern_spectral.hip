@@ -13,8 +13,9 @@
 //   x = L^{-T} Z diag(1 / (1 + tau_D,e lambda)) Z^T L^T (u_hat - (s/|J|) Mh^{-1} g).
 // Mh^{-1}, L^T and L^{-T} are sweeps with 1-D matrices; Z^T and Z are dense
 // products shared by all cells of a layer, so a workgroup takes a tile of NC
-// cells of one layer and runs both products as a small GEMM out of LDS.  The
-// result is exact up to rounding: no iteration, every cell the same work.
+// cells of one layer and runs both products out of LDS, on the FP64 matrix
+// cores for 16-cell tiles (a vector product for the 8-cell tiles of k = 5).
+// The result is exact up to rounding: no iteration, every cell the same work.
 #include <algorithm>
 #include <thread>
 #include <vector>

@@ -35,32 +35,7 @@ __device__ __forceinline__ void tile_sweep(double* T, const double* Mt, int tid)
   }
 }
 
-// acc[i][j] = sum_k Z[k * N + r_i] T[k * LD + cg * CPT + j], r_i = rl + 64 i.
-template <int N, int LD, int RPT, int CPT>
-__device__ __forceinline__ void tile_gemm(const double* T, const double* __restrict__ Z, double (&acc)[RPT][CPT],
-                                          int rl, int cg) {
-#pragma unroll
-  for (int i = 0; i < RPT; ++i)
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) acc[i][j] = 0.0;
-#pragma unroll 8
-  for (int k = 0; k < N; ++k) {
-    double a[CPT];
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) a[j] = T[k * LD + cg * CPT + j];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = rl + 64 * i;
-      if (i < RPT - 1 || r < N) {
-        const double z = Z[(size_t)k * N + r];
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) acc[i][j] = fma(z, a[j], acc[i][j]);
-      }
-    }
-  }
-}
-
-// Split variant: wavefront wv takes row chunks rw + WR i (rw = wv % WR) and
+// Vector product: wavefront wv takes row chunks rw + WR i (rw = wv % WR) and
 // the columns cw * CPW .. cw * CPW + CPW - 1 (cw = wv / WR), so each Z entry
 // is loaded by 4 / WR wavefronts and each tile value read by WR of them:
 // acc[i][j] = sum_k Z[k * N + r_i] T[k * LD + cw * CPW + j], r_i = 64 (rw + WR i) + lane.
