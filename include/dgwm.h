@@ -292,15 +292,11 @@ int dg_apply_divdiv(const dg_mesh* mesh, const double* tau_d, const double* u, d
  * M_e the velocity mass matrix and D_e the div-div penalty with tau_d (as in
  * dg_apply_inverse_mass and dg_apply_divdiv), g = P p the pressure gradient
  * term (dg_apply_pressure_gradient; with scale = dt/gamma_0 this is the
- * projection u^ - dt/gamma_0 grad p of the paper's scheme).  Cells without
- * enrichment, and enriched cells for k_u <= 4, are solved directly (exact up
- * to rounding): per distinct cell height the whitened div-div form is
- * diagonalised once, so that a cell's solve is two dense products shared by
- * its layer plus 1-D sweeps; enriched cells add a 3 x 3 Schur complement on
- * the enrichment unknowns.  Enriched cells at k_u = 5 are solved by
- * conjugate gradients preconditioned with their own M_e^{-1}, until
- * (r, M^{-1} r) has fallen by 1e-28 or after 200 iterations; the cap binds
- * only for tau_D,e / h^2 far beyond the scale of eq. tauD.
+ * projection u^ - dt/gamma_0 grad p of the paper's scheme).  Every cell is
+ * solved directly (exact up to rounding, no iteration): per distinct cell
+ * height the whitened div-div form is diagonalised once, so that a cell's
+ * solve is two dense products shared by its layer plus 1-D sweeps; enriched
+ * cells add a 3 x 3 Schur complement on the enrichment unknowns.
  * The first call on a mesh computes the per-layer tables on the host and
  * waits for their copy to the device (host-synchronous once; about a second
  * at k_u = 4).  The enriched cells' psi-dependent parts are cached until the

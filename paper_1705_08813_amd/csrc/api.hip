@@ -25,9 +25,6 @@ struct WsLayout {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// per-cell CG of the projection step: stop when (r, M^{-1} r) fell by rtol^2
-constexpr int kProjStepMaxIt = 200;
-constexpr double kProjStepRtol = 1e-14;
 
 // Inverse of the 1-D mass matrix M_ij = sum_q w_q N_i(g_q) N_j(g_q) of a
 // Gauss rule with nq >= np points (symmetric positive definite), by
@@ -465,8 +462,7 @@ int dg_projection_step(const dg_mesh* m, const double* tau_d, const double* u_ha
   if (x == u_hat || x == g) return set_error(DG_ERR_ARG, "x must not alias u_hat or g");
   if (!aligned256(tau_d) || !aligned256(u_hat) || !aligned256(g) || !aligned256(x))
     return set_error(DG_ERR_ARG, "tau_d, u_hat, g and x must be 256-byte aligned");
-  return launch_projection_step(m, tau_d, u_hat, g, scale, x, kProjStepMaxIt, kProjStepRtol,
-                                static_cast<hipStream_t>(stream));
+  return launch_projection_step(m, tau_d, u_hat, g, scale, x, static_cast<hipStream_t>(stream));
 }
 
 int dg_enrichment_active(const dg_mesh* m, int32_t* flags, void* stream) {

@@ -236,7 +236,7 @@ void spectral_pointers(const dg_mesh* m, const double** mats, const double** slo
 int launch_spectral_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
                          double* x, hipStream_t s);
 int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
-                           double* x, int max_it, double rtol, hipStream_t s);
+                           double* x, hipStream_t s);
 // x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)
 int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s);
 // u_new = L2 projection of u_old from the space of psi_prev onto that of psi

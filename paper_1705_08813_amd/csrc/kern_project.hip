@@ -404,258 +404,14 @@ __global__ __launch_bounds__(kImThreads) void invmass_kernel(const InvMassArgs A
 }
 
 // ---------------------------------------------------------------------------
-// Element-wise projection step (Sec. 4.2, eq. projectionspat):
-//   (M_e + D_e) x = M_e u_hat - scale g,   D_e(v, w) = (div v, tau_D,e div w)_e,
-// g = P p given.  This iterative form serves the enriched cells at k = 5,
-// whose tile and point fields exceed the LDS of the direct bordered solve
-// below (cells without enrichment always take the direct per-layer solve):
-// per cell, preconditioned CG with the cell's own M^{-1} as
-// preconditioner; all vectors of the cell stay in LDS, the inner products
-// are fixed-order workgroup sums (every lane takes the same branch), and the
-// iteration stops when (r, M^{-1} r) has dropped below rtol^2 times its
-// initial value or after max_it iterations.
-
 template <int NP, int NQ>
 using MSt = ct::MatS<NP, NQ>;
 template <int NP, int NQ>
 using MDt = ct::MatSd<NP, NQ>;
 
-struct StepArgs {
-  InvMassArgs im;          // mesh, tables, psi, caches; im.r / im.x unused
-  const double* tau_d;     // [cell]
-  const double* u_hat;
-  const double* g;
-  double scale, rtol2;
-  int max_it;
-  double* x;
-};
-
-template <int NP, int NQ, int NQY>
-struct StepLds {
-  static constexpr int NP3 = NP * NP * NP, NV = 3 * NP3 + 3, NPT = NQ * NQY * NQ;
-  double x[NV], r[NV], z[NV], p[NV], q[NV];
-  double w0[3 * NPT], w1[3 * NPT];
-  double K[NP * NP], Ky[NP * NP], Ki[NP * NP], Kiy[NP * NP];  // forward and inverse 1-D mass matrices
-  double a[NP3], m[NP3];                                        // enriched cells: cached polynomial parts
-  double red[4 * (kPrjThreads / 64)];
-};
-
-// out = M in (LDS vectors of NV entries; enriched cells add the psi coupling).
-template <int NP, int NQ, int NQY, bool ENR>
-__device__ __forceinline__ void step_mass(StepLds<NP, NQ, NQY>& L, const double* in, double* out, double detJ,
-                                          double mee, int tid) {
-  constexpr int NP3 = NP * NP * NP;
-  sweep<0, NP, NP, NP, NP, false, false>(in, NP3, L.w0, NP3, L.K, 1.0, 3);
-  __syncthreads();
-  sweep<1, NP, NP, NP, NP, false, false>(L.w0, NP3, L.w1, NP3, L.Ky, 1.0, 3);
-  __syncthreads();
-  sweep<2, NP, NP, NP, NP, false, false>(L.w1, NP3, out, NP3, L.K, detJ, 3);
-  if (ENR) {
-    double d[3] = {0.0, 0.0, 0.0};
-    for (int B = tid; B < NP3; B += kPrjThreads) {
-      d[0] += L.m[B] * in[B];
-      d[1] += L.m[B] * in[NP3 + B];
-      d[2] += L.m[B] * in[2 * NP3 + B];
-    }
-    block_sum<3>(d, L.red, tid);  // (its barriers also finish the z sweep)
-    for (int it = tid; it < 3 * NP3; it += kPrjThreads) out[it] += detJ * L.m[it % NP3] * in[3 * NP3 + it / NP3];
-    if (tid < 3) out[3 * NP3 + tid] = detJ * (d[tid] + mee * in[3 * NP3 + tid]);
-  }
-  __syncthreads();
-}
-
-// out += D in: f = w |J| tau div(in) at the points, tested with div v.
-template <int NP, int NQ, int NQY, bool ENR>
-__device__ __forceinline__ void step_divdiv(StepLds<NP, NQ, NQY>& L, const StepArgs& S, int64_t enr,
-                                            const double* in, double* out, const double* h, double tau, int tid) {
-  constexpr int NP3 = NP * NP * NP, NPT = NQ * NQY * NQ;
-  constexpr auto& tq = ct::tab<NP, NQ>;
-  constexpr auto& ty = ct::tab<NP, NQY>;
-  sweep_c<0, NP, NP, NP, NQ, false, false, MDt<NP, NQ>>(in, NP3, L.w0, NPT, 1.0, 1, 0);
-  sweep_c<0, NP, NP, NP, NQ, false, false, MSt<NP, NQ>>(in + NP3, NP3, L.w0 + NPT, NPT, 1.0, 1, 64);
-  sweep_c<0, NP, NP, NP, NQ, false, false, MSt<NP, NQ>>(in + 2 * NP3, NP3, L.w0 + 2 * NPT, NPT, 1.0, 1, 128);
-  __syncthreads();
-  sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(L.w0, NPT, L.w1, NPT, 1.0, 1, 0);
-  sweep_c<1, NQ, NP, NP, NQY, false, false, MDt<NP, NQY>>(L.w0 + NPT, NPT, L.w1 + NPT, NPT, 1.0, 1, 64);
-  sweep_c<1, NQ, NP, NP, NQY, false, false, MSt<NP, NQY>>(L.w0 + 2 * NPT, NPT, L.w1 + 2 * NPT, NPT, 1.0, 1, 128);
-  __syncthreads();
-  sweep_c<2, NQ, NQY, NP, NQ, false, false, MSt<NP, NQ>>(L.w1, NPT, L.w0, NPT, 1.0, 1, 0);
-  sweep_c<2, NQ, NQY, NP, NQ, false, false, MSt<NP, NQ>>(L.w1 + NPT, NPT, L.w0 + NPT, NPT, 1.0, 1, 64);
-  sweep_c<2, NQ, NQY, NP, NQ, false, false, MDt<NP, NQ>>(L.w1 + 2 * NPT, NPT, L.w0 + 2 * NPT, NPT, 1.0, 1, 128);
-  __syncthreads();
-  const double sc = h[0] * h[1] * h[2] * tau;
-  double ve[3] = {0.0, 0.0, 0.0};
-  for (int q = tid; q < NPT; q += kPrjThreads) {
-    const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
-    double dv = L.w0[q] / h[0] + L.w0[NPT + q] / h[1] + L.w0[2 * NPT + q] / h[2];
-    const double* ps = ENR ? S.im.psi + (enr * S.im.psi_pts + q) * 4 : nullptr;
-    if (ENR) dv += ps[1] * in[3 * NP3] + ps[2] * in[3 * NP3 + 1] + ps[3] * in[3 * NP3 + 2];
-    const double f = tq.w[qx] * ty.w[qy] * tq.w[qz] * sc * dv;
-    if (ENR) {
-      ve[0] += ps[1] * f;
-      ve[1] += ps[2] * f;
-      ve[2] += ps[3] * f;
-    }
-    L.w1[q] = f / h[0];
-    L.w1[NPT + q] = f / h[1];
-    L.w1[2 * NPT + q] = f / h[2];
-  }
-  __syncthreads();
-  sweep_c<0, NQ, NQY, NQ, NP, true, false, MDt<NP, NQ>>(L.w1, NPT, L.w0, NPT, 1.0, 1, 0);
-  sweep_c<0, NQ, NQY, NQ, NP, true, false, MSt<NP, NQ>>(L.w1 + NPT, NPT, L.w0 + NPT, NPT, 1.0, 1, 64);
-  sweep_c<0, NQ, NQY, NQ, NP, true, false, MSt<NP, NQ>>(L.w1 + 2 * NPT, NPT, L.w0 + 2 * NPT, NPT, 1.0, 1, 128);
-  __syncthreads();
-  sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(L.w0, NPT, L.w1, NPT, 1.0, 1, 0);
-  sweep_c<1, NP, NQY, NQ, NP, true, false, MDt<NP, NQY>>(L.w0 + NPT, NPT, L.w1 + NPT, NPT, 1.0, 1, 64);
-  sweep_c<1, NP, NQY, NQ, NP, true, false, MSt<NP, NQY>>(L.w0 + 2 * NPT, NPT, L.w1 + 2 * NPT, NPT, 1.0, 1, 128);
-  __syncthreads();
-  sweep_c<2, NP, NP, NQ, NP, true, true, MSt<NP, NQ>>(L.w1, NPT, out, NP3, 1.0, 1, 0);
-  sweep_c<2, NP, NP, NQ, NP, true, true, MSt<NP, NQ>>(L.w1 + NPT, NPT, out + NP3, NP3, 1.0, 1, 64);
-  sweep_c<2, NP, NP, NQ, NP, true, true, MDt<NP, NQ>>(L.w1 + 2 * NPT, NPT, out + 2 * NP3, NP3, 1.0, 1, 128);
-  if (ENR) {
-    block_sum<3>(ve, L.red, tid);
-    if (tid < 3) out[3 * NP3 + tid] += ve[tid];
-  }
-  __syncthreads();
-}
-
-// out = M^{-1} in (regular: tensor inverse; enriched: Schur complement with the cache).
-template <int NP, int NQ, int NQY, bool ENR>
-__device__ __forceinline__ void step_minv(StepLds<NP, NQ, NQY>& L, const double* in, double* out, double idet,
-                                          double inv_rr, int tid) {
-  constexpr int NP3 = NP * NP * NP;
-  double xt[3] = {0.0, 0.0, 0.0};
-  if (ENR) {
-    double d[3] = {0.0, 0.0, 0.0};
-    for (int B = tid; B < NP3; B += kPrjThreads) {
-      d[0] += L.a[B] * in[B];
-      d[1] += L.a[B] * in[NP3 + B];
-      d[2] += L.a[B] * in[2 * NP3 + B];
-    }
-    block_sum<3>(d, L.red, tid);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) xt[c] = (in[3 * NP3 + c] - d[c]) * inv_rr * idet;
-  }
-  sweep<0, NP, NP, NP, NP, false, false>(in, NP3, L.w0, NP3, L.Ki, 1.0, 3);
-  __syncthreads();
-  sweep<1, NP, NP, NP, NP, false, false>(L.w0, NP3, L.w1, NP3, L.Kiy, 1.0, 3);
-  __syncthreads();
-  sweep<2, NP, NP, NP, NP, false, false>(L.w1, NP3, out, NP3, L.Ki, idet, 3);
-  __syncthreads();
-  if (ENR) {
-    for (int it = tid; it < 3 * NP3; it += kPrjThreads) {
-      const int c = it / NP3;
-      out[it] -= L.a[it - c * NP3] * (c == 0 ? xt[0] : (c == 1 ? xt[1] : xt[2]));
-    }
-    if (tid < 3) out[3 * NP3 + tid] = tid == 0 ? xt[0] : (tid == 1 ? xt[1] : xt[2]);
-    __syncthreads();
-  }
-}
-
-template <int NP, int NQ, int NQY, bool ENR>
-__device__ __forceinline__ double step_dot(StepLds<NP, NQ, NQY>& L, const double* u, const double* v, int tid) {
-  constexpr int N = ENR ? 3 * NP * NP * NP + 3 : 3 * NP * NP * NP;
-  double s[1] = {0.0};
-  for (int i = tid; i < N; i += kPrjThreads) s[0] += u[i] * v[i];
-  block_sum<1>(s, L.red, tid);
-  __syncthreads();  // red is reused by the next sum
-  return s[0];
-}
-
-template <int NP, int NQ, int NQY, bool ENR>
-__global__ __launch_bounds__(kPrjThreads) void projection_step_kernel(const StepArgs S, int layer_lo, int nlayers) {
-  constexpr int NP3 = NP * NP * NP, NV = 3 * NP3 + 3;
-  __shared__ StepLds<NP, NQ, NQY> L;
-  const InvMassArgs& A = S.im;
-  const int tid = threadIdx.x;
-  const int64_t b = blockIdx.x;
-  int64_t e;
-  int ey;
-  if (ENR) {
-    e = enriched_cell_index(A.nx, A.ny, A.lower_slot, A.nslots, b);
-    ey = (int)((e / A.nx) % A.ny);
-  } else {
-    const int ex = (int)(b % A.nx);
-    const int64_t t0 = b / A.nx;
-    ey = layer_lo + (int)(t0 % nlayers);
-    e = ex + (int64_t)A.nx * (ey + (int64_t)A.ny * (t0 / nlayers));
-  }
-  const double h[3] = {1.0 / A.ihx, 1.0 / A.ihy[ey], 1.0 / A.ihz};
-  const double detJ = h[0] * h[1] * h[2], idet = A.ihx * A.ihy[ey] * A.ihz;
-  const double tau = S.tau_d[e];
-  // 1-D mass matrices of the rules (forward from the compile-time tables, inverse from the mesh)
-  {
-    constexpr auto& tq = ct::tab<NP, NQ>;
-    constexpr auto& ty = ct::tab<NP, NQY>;
-    for (int ij = tid; ij < NP * NP; ij += kPrjThreads) {
-      const int i = ij / NP, j = ij - i * NP;
-      double kx = 0.0, ky = 0.0;
-      for (int q = 0; q < NQ; ++q) kx += tq.w[q] * tq.S[q][i] * tq.S[q][j];
-      for (int q = 0; q < NQY; ++q) ky += ty.w[q] * ty.S[q][i] * ty.S[q][j];
-      L.K[ij] = kx;
-      L.Ky[ij] = ky;
-      L.Ki[ij] = A.minv[ij];
-      L.Kiy[ij] = ENR ? A.minv[NP * NP + ij] : A.minv[ij];
-    }
-  }
-  double inv_rr = 0.0, mee = 0.0;
-  const int64_t eo = A.ncell * 3 * NP3 + b * 3;
-  if (ENR) {
-    const double* ap = A.apoly + b * apoly_stride(NP3);
-    for (int B = tid; B < NP3; B += kPrjThreads) {
-      L.a[B] = ap[B];
-      L.m[B] = ap[NP3 + 1 + B];
-    }
-    inv_rr = ap[NP3];
-    mee = ap[2 * NP3 + 1];
-  }
-  // p <- u_hat (cell block), q <- g
-  const double* ue = S.u_hat + e * 3 * NP3;
-  const double* ge = S.g + e * 3 * NP3;
-  for (int i = tid; i < 3 * NP3; i += kPrjThreads) {
-    L.p[i] = ue[i];
-    L.q[i] = ge[i];
-    L.x[i] = 0.0;
-  }
-  if (tid < 3) {
-    L.p[3 * NP3 + tid] = ENR ? S.u_hat[eo + tid] : 0.0;
-    L.q[3 * NP3 + tid] = ENR ? S.g[eo + tid] : 0.0;
-    L.x[3 * NP3 + tid] = 0.0;
-  }
-  __syncthreads();
-  // r = b = M u_hat - scale g
-  step_mass<NP, NQ, NQY, ENR>(L, L.p, L.r, detJ, mee, tid);
-  for (int i = tid; i < NV; i += kPrjThreads) L.r[i] -= S.scale * L.q[i];
-  __syncthreads();
-  step_minv<NP, NQ, NQY, ENR>(L, L.r, L.z, idet, inv_rr, tid);
-  for (int i = tid; i < NV; i += kPrjThreads) L.p[i] = L.z[i];
-  __syncthreads();
-  double rz = step_dot<NP, NQ, NQY, ENR>(L, L.r, L.z, tid);
-  const double stop = S.rtol2 * rz;
-  for (int it = 0; it < S.max_it && rz > stop; ++it) {
-    step_mass<NP, NQ, NQY, ENR>(L, L.p, L.q, detJ, mee, tid);
-    step_divdiv<NP, NQ, NQY, ENR>(L, S, b, L.p, L.q, h, tau, tid);
-    const double pq = step_dot<NP, NQ, NQY, ENR>(L, L.p, L.q, tid);
-    const double alpha = rz / pq;
-    for (int i = tid; i < NV; i += kPrjThreads) {
-      L.x[i] += alpha * L.p[i];
-      L.r[i] -= alpha * L.q[i];
-    }
-    __syncthreads();
-    step_minv<NP, NQ, NQY, ENR>(L, L.r, L.z, idet, inv_rr, tid);
-    const double rz1 = step_dot<NP, NQ, NQY, ENR>(L, L.r, L.z, tid);
-    const double beta = rz1 / rz;
-    rz = rz1;
-    for (int i = tid; i < NV; i += kPrjThreads) L.p[i] = L.z[i] + beta * L.p[i];
-    __syncthreads();
-  }
-  double* xe = S.x + e * 3 * NP3;
-  for (int i = tid; i < 3 * NP3; i += kPrjThreads) xe[i] = L.x[i];
-  if (ENR && tid < 3) S.x[eo + tid] = L.x[3 * NP3 + tid];
-}
-
-
-// Direct solve of the projection step in enriched cells (NP <= 5).  The
+// Element-wise projection step (Sec. 4.2, eq. projectionspat),
+//   (M_e + D_e) x = M_e u_hat - scale g,   D_e(v, w) = (div v, tau_D,e div w)_e,
+// solved directly in enriched cells.  The
 // polynomial block of an enriched cell is the block of a cell without
 // enrichment of the same height (both Gauss rules integrate the polynomial
 // products exactly), P = |J| (Mh + tau Dh), solved with the layer's spectral
@@ -1066,42 +822,22 @@ int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_
   return set_error(DG_ERR_UNSUPPORTED, "inverse mass: degree not compiled");
 }
 
-namespace {
-template <int P, int Q, int W>
-int launch_enriched_step(const BorderArgs& B, const StepArgs& S, int64_t nenr, int grid, hipStream_t s) {
-  if constexpr (P <= 5)
-    hipLaunchKernelGGL((bordered_step_kernel<P, Q, W>), dim3((unsigned)grid), dim3(kSpecThreads), 0, s, B);
-  else  // the tile and the point fields exceed the LDS: per-cell CG
-    hipLaunchKernelGGL((projection_step_kernel<P, Q, W, true>), dim3((unsigned)nenr), dim3(kPrjThreads), 0, s, S, 0,
-                       0);
-  return check_hip(hipGetLastError(), "projection step kernel launch");
-}
-}  // namespace
 
 int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
-                           double* x, int max_it, double rtol, hipStream_t s) {
+                           double* x, hipStream_t s) {
   int rc = ensure_spectral_tables(m, s);
   // cells without enrichment: direct solve per layer
   if (!rc) rc = launch_spectral_step(m, tau_d, u_hat, g, scale, x, s);
   if (rc || m->nenr == 0) return rc;
-  StepArgs S;
-  S.im = invmass_args(m, nullptr, nullptr);
-  S.tau_d = tau_d;
-  S.u_hat = u_hat;
-  S.g = g;
-  S.scale = scale;
-  S.rtol2 = rtol * rtol;
-  S.max_it = max_it;
-  S.x = x;
-  rc = ensure_psi_poly(m, S.im, s);
+  const InvMassArgs IA = invmass_args(m, nullptr, nullptr);
+  rc = ensure_psi_poly(m, IA, s);
   if (rc) return rc;
-  if (m->np_u <= 5 && !m->coup_ok) {
+  if (!m->coup_ok) {
     bool launched = false;
 #define X(p, q, w)                                                                                               \
     if (!launched && m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                        \
-      if constexpr (p <= 5)                                                                                      \
-        hipLaunchKernelGGL((coupling_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kSpecThreads), 0, s, S.im, \
-                           m->coup);                                                                             \
+      hipLaunchKernelGGL((coupling_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kSpecThreads), 0, s, IA,     \
+                         m->coup);                                                                               \
       launched = true;                                                                                           \
     }
     DG_PRJ_COMBOS(X)
@@ -1113,7 +849,7 @@ int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* 
   }
   BorderArgs B;
   B.coup = m->coup;
-  B.im = S.im;
+  B.im = IA;
   spectral_pointers(m, &B.mats, &B.slots, &B.map);
   B.tau_d = tau_d;
   B.u_hat = u_hat;
@@ -1125,8 +861,11 @@ int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* 
   if (tiles * m->n_enr_layers > INT32_MAX / 2) return set_error(DG_ERR_ARG, "projection step: mesh too large");
   B.tiles = (int)tiles;
   const int grid = (int)(tiles * m->n_enr_layers);
-#define X(p, q, w)                                                        \
-  if (m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) return launch_enriched_step<p, q, w>(B, S, m->nenr, grid, s);
+#define X(p, q, w)                                                                                       \
+  if (m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                               \
+    hipLaunchKernelGGL((bordered_step_kernel<p, q, w>), dim3((unsigned)grid), dim3(kSpecThreads), 0, s, B); \
+    return check_hip(hipGetLastError(), "projection step kernel launch");                                \
+  }
   DG_PRJ_COMBOS(X)
 #undef X
   return set_error(DG_ERR_UNSUPPORTED, "projection step: (k_u+1, nq_u, nq_wn) combination not compiled");

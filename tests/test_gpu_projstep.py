@@ -2,8 +2,9 @@
 the oracle's dense per-cell solve, through the C ABI.
 
 Per cell, ||x_gpu - x_oracle||_inf <= tol ||x_oracle||_inf with tol = 1e-11 in
-cells without enrichment (the kernel's CG stops at a relative (r, M^{-1} r) of
-1e-28) and max(1e-11, 64 eps cond(M_cell)) in enriched cells, whose mass
+cells without enrichment (both sides are direct solves; the kernel's passes
+through an orthogonal eigenbasis of the whitened block, accurate to about
+1e-13) and max(1e-11, 64 eps cond(M_cell)) in enriched cells, whose mass
 blocks have condition numbers up to 1e8 (as for the inverse mass).
 """
 import numpy as np
@@ -118,7 +119,7 @@ def test_projection_step_rejects_bad_arguments():
 
 def test_projection_step_without_penalty_is_inverse_mass():
     """tau_D = 0 on the bench mesh: (M) x = M u_hat - s g, so x = u_hat - s M^{-1} g
-    in every cell (direct solve in regular cells, CG in enriched ones)."""
+    in every cell (direct per-layer solve, bordered in enriched cells)."""
     wl = PRESETS["large"]
     cfg = wl.mesh
     print("[gpu] projection step, zero penalty, large mesh", flush=True)
