@@ -227,8 +227,7 @@ size_t spectral_table_doubles(const dg_mesh& m) {
 
 // Host: 1-D factors, whitened div-div forms, their eigendecompositions; copies
 // everything into m->spec (synchronous on s).
-int ensure_spectral_tables(const dg_mesh* m, hipStream_t s) {
-  if (m->spec_ok) return DG_OK;
+static int build_spectral_tables(const dg_mesh* m, hipStream_t s) {
   const dg_mesh_params& P = m->P;
   const int np = m->np_u, nq = P.nq_u, np3 = np * np * np, n = 3 * np3, npt = nq * nq * nq;
   std::vector<int> map;
@@ -312,15 +311,31 @@ int ensure_spectral_tables(const dg_mesh* m, hipStream_t s) {
       }
     for (int r = 0; r < n; ++r) L[r] = std::max(lam[r], 0.0);  // positive semidefinite form
   };
+  // slots t, t + nth, ... per worker; an allocation failure marks the slot (-2) instead of escaping the thread,
+  // and workers that cannot be started run on this thread
+  auto run = [&](int t, int nth) {
+    for (int slot = t; slot < ns; slot += nth) {
+      try {
+        work(slot);
+      } catch (...) {
+        sweeps[slot] = -2;
+      }
+    }
+  };
   const int nth = std::max(1, std::min<int>(ns, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
   std::vector<std::thread> pool;
-  for (int t = 0; t < nth; ++t)
-    pool.emplace_back([&, t] {
-      for (int slot = t; slot < ns; slot += nth) work(slot);
-    });
+  int started = 0;
+  try {
+    pool.reserve(nth);
+    for (; started < nth; ++started) pool.emplace_back(run, started, nth);
+  } catch (...) {
+  }
+  for (int t = started; t < nth; ++t) run(t, nth);
   for (auto& th : pool) th.join();
-  for (int slot = 0; slot < ns; ++slot)
+  for (int slot = 0; slot < ns; ++slot) {
+    if (sweeps[slot] == -2) return set_error(DG_ERR_ARG, "projection step: host memory for the layer tables refused");
     if (sweeps[slot] < 0) return set_error(DG_ERR_NOT_CONVERGED, "projection step: eigendecomposition did not converge");
+  }
   int32_t* mp = reinterpret_cast<int32_t*>(host.data() + head + ns * per);
   for (int j = 0; j < P.ny; ++j) mp[j] = map[j];
   int rc = check_hip(hipMemcpyAsync(m->spec, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, s),
@@ -328,6 +343,15 @@ int ensure_spectral_tables(const dg_mesh* m, hipStream_t s) {
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "projection step tables");
   if (!rc) m->spec_ok = 1;
   return rc;
+}
+
+int ensure_spectral_tables(const dg_mesh* m, hipStream_t s) {
+  if (m->spec_ok) return DG_OK;
+  try {
+    return build_spectral_tables(m, s);
+  } catch (...) {  // host allocations: no exception crosses the C ABI
+    return set_error(DG_ERR_ARG, "projection step: host memory for the layer tables refused");
+  }
 }
 
 void spectral_pointers(const dg_mesh* m, const double** mats, const double** slots, const int32_t** map) {
