@@ -155,7 +155,7 @@ struct dg_mesh {
   double* minv;           // inverse 1-D mass matrices [2][np_u][np_u]: x/z rule, wall-normal rule
   double* apoly;          // [enr][2 np_u^3 + 2]: polynomial part of the current psi (inverse mass / projection step cache)
   mutable int apoly_ok = 0;  // apoly matches the current psi table
-  double* coup;           // [enr][9 np_u^3 + 6]: projection step couplings of the current psi (np_u <= 5)
+  double* coup;           // [enr][9 np_u^3 + 6]: projection step couplings of the current psi
   mutable int coup_ok = 0;   // coup matches the current psi table
   double* spec;           // projection step, cells without enrichment: [3][np][np] 1-D factors, then per
                           // distinct layer height Z, Z^T, lambda of the whitened div-div form, then the
