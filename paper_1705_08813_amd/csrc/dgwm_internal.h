@@ -158,7 +158,7 @@ struct dg_mesh {
   double* coup;           // [enr][9 np_u^3 + 6]: projection step couplings of the current psi
   mutable int coup_ok = 0;   // coup matches the current psi table
   double* spec;           // projection step, cells without enrichment: [3][np][np] 1-D factors, then per
-                          // distinct layer height Z, Z^T, lambda of the whitened div-div form, then the
+                          // distinct layer height (L Z)^T, L^{-T} Z, lambda of the whitened div-div form, then the
                           // int32 layer -> slot map (filled on the first projection step)
   mutable int spec_ok = 0;   // spec filled
   double* diag;           // Poisson diagonal (FP64)

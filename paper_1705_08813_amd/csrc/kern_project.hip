@@ -434,7 +434,7 @@ using MDt = ct::MatSd<NP, NQ>;
 struct BorderArgs {
   InvMassArgs im;
   const double* mats;   // K^{-1}, C^T, C^{-T}
-  const double* slots;  // per layer slot: Z, Z^T, lambda
+  const double* slots;  // per layer slot: (L Z)^T and L^{-T} Z tables, lambda
   const int32_t* map;
   const double* tau_d;
   const double* u_hat;
@@ -576,12 +576,6 @@ __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const Borde
     T[k * LD + 4 * c] += S.u_hat[cell_of(c) * N + k] + a * S.u_hat[A.ncell * N + 3 * b + cc];
   }
   __syncthreads();
-  tile_sweep<NP, NC, 0>(T, Mt + NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 1>(T, Mt + NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 2>(T, Mt + NP2, tid);
-  __syncthreads();
   // per-cell scalars: wavefront wv <-> cell wv
   __shared__ double TAU[4], Gp[2][4][9];
   const bool valid = wv < nc;
@@ -698,12 +692,6 @@ __global__ __launch_bounds__(kSpecThreads) void bordered_step_kernel(const Borde
 #pragma unroll
       for (int m = 0; m < 2; ++m) T[r * LD + 4 * (2 * cw + m)] = acc[i][4 * m];
   }
-  __syncthreads();
-  tile_sweep<NP, NC, 0>(T, Mt + 2 * NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 1>(T, Mt + 2 * NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 2>(T, Mt + 2 * NP2, tid);
   __syncthreads();
   // back to the psi basis: x_p = x'_p - a x_e
   for (int it = tid; it < 4 * N; it += kSpecThreads) {

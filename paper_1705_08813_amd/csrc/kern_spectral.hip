@@ -11,8 +11,9 @@
 // whitened form  L^{-1} Dh L^{-T} = Z diag(lambda) Z^T  (once per distinct
 // layer height, on the host, by the cyclic Jacobi method),
 //   x = L^{-T} Z diag(1 / (1 + tau_D,e lambda)) Z^T L^T (u_hat - (s/|J|) Mh^{-1} g).
-// Mh^{-1}, L^T and L^{-T} are sweeps with 1-D matrices; Z^T and Z are dense
-// products shared by all cells of a layer, so a workgroup takes a tile of NC
+// Mh^{-1} is a sweep with 1-D matrices; L^T and L^{-T} are folded into the
+// layer's tables, (L Z)^T and L^{-T} Z, which are dense products shared by
+// all cells of a layer, so a workgroup takes a tile of NC
 // cells of one layer and runs both products out of LDS, on the FP64 matrix
 // cores for 16-cell tiles (a vector product for the 8-cell tiles of k = 5).
 // The result is exact up to rounding: no iteration, every cell the same work.
@@ -40,7 +41,7 @@ struct SpecArgs {
   double hx, hz;
   const double* hy;     // [ny] cell heights
   const double* mats;   // [3][np][np]: K^{-1}, C^T, C^{-T} (row-major, out_a = sum_i M[a][i] in_i)
-  const double* slots;  // [slot][2 n^2 + n]: Z (row-major), Z^T (row-major), lambda
+  const double* slots;  // [slot][2 n^2 + n]: A1[k][r] = (L Z)[k][r], A2[k][r] = (L^{-T} Z)[r][k], lambda
   const int32_t* map;   // [ny] slot of each layer
   const double* tau_d;
   const double* u_hat;
@@ -92,13 +93,7 @@ __global__ __launch_bounds__(kSpecThreads) void spectral_step_kernel(const SpecA
     T[k * LD + c] = (c < nc ? A.u_hat[cell(c) * N + k] : 0.0) - f * T[k * LD + c];
   }
   __syncthreads();
-  // L^T (u_hat - f Mh^{-1} g)
-  tile_sweep<NP, NC, 0>(T, Mt + NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 1>(T, Mt + NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 2>(T, Mt + NP2, tid);
-  __syncthreads();
+  // (the factors L^T before and L^{-T} after the products are folded into the tables)
   const double* Zs = A.slots + (size_t)A.map[layer] * (2 * (size_t)N * N + N);
   const double* lam = Zs + 2 * (size_t)N * N;
   const int lane = tid & 63, wv = tid >> 6;
@@ -152,13 +147,6 @@ __global__ __launch_bounds__(kSpecThreads) void spectral_step_kernel(const SpecA
     }
     __syncthreads();
   }
-  __syncthreads();
-  // L^{-T}
-  tile_sweep<NP, NC, 0>(T, Mt + 2 * NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 1>(T, Mt + 2 * NP2, tid);
-  __syncthreads();
-  tile_sweep<NP, NC, 2>(T, Mt + 2 * NP2, tid);
   __syncthreads();
   for (int idx = tid; idx < NC * N; idx += kSpecThreads) {
     const int c = idx / N, k = idx - c * N;
@@ -301,14 +289,38 @@ static int build_spectral_tables(const dg_mesh* m, hipStream_t s) {
       }
     }
     sweeps[slot] = sym_eig_jacobi(n, Bm, lam, vt);
-    double* Z = host.data() + head + slot * per;
-    double* ZT = Z + (size_t)n * n;
-    double* L = ZT + (size_t)n * n;
-    for (int k = 0; k < n; ++k)
-      for (int r = 0; r < n; ++r) {
-        Z[(size_t)k * n + r] = vt[(size_t)r * n + k];  // Z[k][r]: entry k of eigenvector r
-        ZT[(size_t)k * n + r] = vt[(size_t)k * n + r];
+    // first product: (L Z)^T, stored as A1[k][r] = (L z_r)[k]; second: L^{-T} Z, stored as A2[k][r] = (L^{-T} z_k)[r]
+    // (z_r eigenvector r; L and L^{-T} applied as 1-D factors along each direction of each component)
+    double* A1 = host.data() + head + slot * per;
+    double* A2 = A1 + (size_t)n * n;
+    double* L = A2 + (size_t)n * n;
+    std::vector<double> v((size_t)n), w((size_t)n);
+    auto along = [&](const std::vector<double>& M, bool transpose, std::vector<double>& x) {
+      for (int dir = 0; dir < 3; ++dir) {
+        const int sd = dir == 0 ? 1 : (dir == 1 ? np : np * np);
+        for (int c = 0; c < 3; ++c)
+          for (int l = 0; l < np * np; ++l) {
+            const int base = c * np3 + (dir == 0 ? l * np : (dir == 1 ? (l % np) + (l / np) * np * np : l));
+            double in[8], out[8];
+            for (int i = 0; i < np; ++i) in[i] = x[base + i * sd];
+            for (int a = 0; a < np; ++a) {
+              double t = 0.0;
+              for (int i = 0; i < np; ++i) t += (transpose ? M[i * np + a] : M[a * np + i]) * in[i];
+              out[a] = t;
+            }
+            for (int a = 0; a < np; ++a) x[base + a * sd] = out[a];
+          }
       }
+    };
+    for (int r = 0; r < n; ++r) {
+      for (int k = 0; k < n; ++k) v[k] = w[k] = vt[(size_t)r * n + k];
+      along(C, false, v);   // L z_r
+      along(Ci, true, w);   // L^{-T} z_r
+      for (int k = 0; k < n; ++k) {
+        A1[(size_t)k * n + r] = v[k];
+        A2[(size_t)r * n + k] = w[k];
+      }
+    }
     for (int r = 0; r < n; ++r) L[r] = std::max(lam[r], 0.0);  // positive semidefinite form
   };
   // slots t, t + nth, ... per worker; an allocation failure marks the slot (-2) instead of escaping the thread,
