@@ -302,7 +302,7 @@ int dg_apply_divdiv(const dg_mesh* mesh, const double* tau_d, const double* u, d
  * at k_u = 4).  The enriched cells' psi-dependent parts are cached until the
  * next wall-shear update, as for dg_apply_inverse_mass.
  *   tau_d: device, nx*ny*nz doubles; u_hat, g, x: device, dg_num_dofs(mesh,
- *   0) doubles, x distinct from u_hat and g.  Flat meshes only.  Fills the
+ *   0) doubles, x distinct from u_hat, g and tau_d.  Flat meshes only.  Fills the
  *   inverse-mass cache on its first call after a wall-shear update (see
  *   dg_apply_inverse_mass).
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP, DG_ERR_NOT_CONVERGED

@@ -459,7 +459,7 @@ int dg_projection_step(const dg_mesh* m, const double* tau_d, const double* u_ha
   if (!m || !tau_d || !u_hat || !g || !x) return set_error(DG_ERR_ARG, "mesh/tau_d/u_hat/g/x is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "projection step: flat meshes only");
   if (!std::isfinite(scale)) return set_error(DG_ERR_ARG, "scale must be finite");
-  if (x == u_hat || x == g) return set_error(DG_ERR_ARG, "x must not alias u_hat or g");
+  if (x == u_hat || x == g || x == tau_d) return set_error(DG_ERR_ARG, "x must not alias u_hat, g or tau_d");
   if (!aligned256(tau_d) || !aligned256(u_hat) || !aligned256(g) || !aligned256(x))
     return set_error(DG_ERR_ARG, "tau_d, u_hat, g and x must be 256-byte aligned");
   return launch_projection_step(m, tau_d, u_hat, g, scale, x, static_cast<hipStream_t>(stream));

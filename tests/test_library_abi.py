@@ -63,6 +63,7 @@ def test_null_handles_are_rejected():
     assert L.dg_apply_velocity_divergence(None, None, None, None) == -1
     assert L.dg_divdiv_tau(None, None, 0.0, None, None) == -1
     assert L.dg_apply_divdiv(None, None, None, None, None) == -1
+    assert L.dg_projection_step(None, None, None, None, 1.0, None, None) == -1
 
 
 def test_large_workspace_fits_hbm():
