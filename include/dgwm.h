@@ -300,7 +300,9 @@ int dg_apply_divdiv(const dg_mesh* mesh, const double* tau_d, const double* u, d
  * The first call on a mesh computes the per-layer tables on the host and
  * waits for their copy to the device (host-synchronous once; about a second
  * at k_u = 4).  The enriched cells' psi-dependent parts are cached until the
- * next wall-shear update, as for dg_apply_inverse_mass.
+ * next wall-shear update, as for dg_apply_inverse_mass.  A call that fills
+ * the tables or the cache writes to the handle: like an update, it must not
+ * overlap other calls on the same handle.
  *   tau_d: device, nx*ny*nz doubles; u_hat, g, x: device, dg_num_dofs(mesh,
  *   0) doubles, x distinct from u_hat, g and tau_d.  Flat meshes only.  Fills the
  *   inverse-mass cache on its first call after a wall-shear update (see
