@@ -77,6 +77,7 @@ def lib():
         L.orc_velocity_divergence.argtypes = [P, _D, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_enrichment_active.argtypes = [P, _D, _D, ctypes.POINTER(ctypes.c_int32)]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
+        L.orc_face_points.argtypes = [P, ctypes.c_int64, ctypes.c_int, _D]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         _LIB = L
@@ -422,3 +423,15 @@ def cell_map(cfg, e, xi):
     det = ctypes.c_double()
     lib().orc_cell_map(ctypes.byref(p), int(e), _ptr(xi), _ptr(X), ctypes.byref(det))
     return X, det.value
+
+
+def face_points(cfg, e, f):
+    """Quadrature points of face f = 2 d + s of cell e (the velocity residual's
+    face rule): X [npts, 3], n w dA [npts, 3] and w dA [npts]."""
+    p = params(cfg)
+    out = np.zeros(7 * 16 * 16)
+    n = lib().orc_face_points(ctypes.byref(p), int(e), int(f), _ptr(out))
+    if n < 0:
+        raise ValueError(f"orc_face_points failed: {n}")
+    o = out[: 7 * n].reshape(n, 7)
+    return o[:, :3].copy(), o[:, 3:6].copy(), o[:, 6].copy()

@@ -313,6 +313,24 @@ static double inv3(const double J[3][3], double Ji[3][3]) {
   return det;
 }
 
+/* Geometry at the point xi of face (d, s) of cell e (xi[d] = s): physical
+ * point X, inverse Jacobian Ji, outward unit normal nv and the area element
+ * dA per unit reference-face area.  Nanson's relation for the map x(xi):
+ * n dA = det(J) J^{-T} N dA_ref with the reference normal N = -e_d (s = 0) or
+ * +e_d (s = 1); the d-th column of J^{-T} is the d-th row of J^{-1}, so
+ * nv = sg Ji[d][:] / |Ji[d][:]| and dA = |det J| |Ji[d][:]|. */
+static void face_point(const ctx *C, int64_t e, int d, int s, const double xi[3], double X[3], double Ji[3][3],
+                       double nv[3], double *dA) {
+  double J[3][3];
+  cell_map(C, e, xi, X, J);
+  double det = fabs(inv3(J, Ji));
+  double sg = s ? 1.0 : -1.0;
+  for (int k = 0; k < 3; ++k) nv[k] = sg * Ji[d][k];
+  double nr = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  for (int k = 0; k < 3; ++k) nv[k] /= nr;
+  *dA = det * nr;
+}
+
 static int cell_enriched(const ctx *C, int ey) {
   if (C->P.fully_periodic) return 0;
   return (ey == 0 && C->P.enrich_lower) || (ey == C->P.ny - 1 && C->P.enrich_upper);
@@ -688,12 +706,10 @@ static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int ab
     double area = 0;
     for (int b = 0; b < n2; ++b)
       for (int a = 0; a < n1; ++a) {
-        double xi[3], X[3], J[3][3], Ji[3][3];
+        double xi[3], X[3], Ji[3][3], nv[3], dA;
         xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
-        cell_map(C, e, xi, X, J);
-        double det = fabs(inv3(J, Ji));
-        double nr = sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
-        area += det * nr * w1[a] * w2[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        area += dA * w1[a] * w2[b];
       }
     double pf = C->P.ip_factor_u * (double)(n) * (double)(n);
     double tauF;
@@ -702,15 +718,10 @@ static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int ab
 
     for (int b = 0; b < n2; ++b)
       for (int a = 0; a < n1; ++a) {
-        double xi[3], xn[3], X[3], J[3][3], Ji[3][3], Xn[3], Jn[3][3], Jin[3][3];
+        double xi[3], xn[3], X[3], Ji[3][3], Xn[3], Jn[3][3], Jin[3][3], nv[3], dA;
         xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
-        cell_map(C, e, xi, X, J);
-        double det = fabs(inv3(J, Ji));
-        double sg = s ? 1.0 : -1.0;
-        double nv[3] = {sg * Ji[d][0], sg * Ji[d][1], sg * Ji[d][2]};
-        double nr = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-        for (int k = 0; k < 3; ++k) nv[k] /= nr;
-        double wf = det * nr * w1[a] * w2[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        double wf = dA * w1[a] * w2[b];
         vel_pt pm, pp;
         eval_vel(C, u, e, xi, Ji, absmode, &pm, bv, bg);
         if (wall) {
@@ -883,15 +894,10 @@ static void grad_cell(const ctx *C, const double *p, int64_t e, double *g, doubl
     face_rule(C, e, nb, t1, t2, &q1, &w1, &n1, &q2, &w2, &n2);
     for (int b = 0; b < n2; ++b)
       for (int a = 0; a < n1; ++a) {
-        double xi[3], X[3], J[3][3], Ji[3][3];
+        double xi[3], X[3], Ji[3][3], nv[3], dA;
         xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
-        cell_map(C, e, xi, X, J);
-        double det = fabs(inv3(J, Ji));
-        double sg = s ? 1.0 : -1.0;
-        double nv[3] = {sg * Ji[d][0], sg * Ji[d][1], sg * Ji[d][2]};
-        double nr = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-        for (int k = 0; k < 3; ++k) nv[k] /= nr;
-        double wf = det * nr * w1[a] * w2[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        double wf = dA * w1[a] * w2[b];
         double pm = eval_p(C, p, e, xi, Ji, pv, pg), pp = pm;
         if (nb >= 0) {
           double xn[3], Xn[3], Jn[3][3], Jin[3][3];
@@ -952,15 +958,10 @@ static void div_cell(const ctx *C, const double *u, int64_t e, double *out, doub
     face_rule(C, e, nb, t1, t2, &q1, &w1, &n1, &q2, &w2, &n2);
     for (int b = 0; b < n2; ++b)
       for (int a = 0; a < n1; ++a) {
-        double xi[3], xn[3], X[3], J[3][3], Ji[3][3], Xn[3], Jn[3][3], Jin[3][3];
+        double xi[3], xn[3], X[3], Ji[3][3], Xn[3], Jn[3][3], Jin[3][3], nv[3], dA;
         xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
-        cell_map(C, e, xi, X, J);
-        double det = fabs(inv3(J, Ji));
-        double sg = s ? 1.0 : -1.0;
-        double nv[3] = {sg * Ji[d][0], sg * Ji[d][1], sg * Ji[d][2]};
-        double nr = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-        for (int k = 0; k < 3; ++k) nv[k] /= nr;
-        double wf = det * nr * w1[a] * w2[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        double wf = dA * w1[a] * w2[b];
         vel_pt pm, pp;
         eval_vel(C, u, e, xi, Ji, 0, &pm, bv, bg);
         if (nb >= 0) {
@@ -1162,25 +1163,18 @@ static void poisson_cell(const ctx *C, const double *p, int64_t e, double *y, in
     double area = 0;
     for (int b = 0; b < nq; ++b)
       for (int a = 0; a < nq; ++a) {
-        double xi[3], X[3], J[3][3], Ji[3][3];
+        double xi[3], X[3], Ji[3][3], nv[3], dA;
         xi[d] = s; xi[t1] = C->qp[a]; xi[t2] = C->qp[b];
-        cell_map(C, e, xi, X, J);
-        double det = fabs(inv3(J, Ji));
-        double nr = sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
-        area += det * nr * C->wp[a] * C->wp[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        area += dA * C->wp[a] * C->wp[b];
       }
     double tauF = C->P.ip_factor_p * (double)n * n * fmax(area / vol_e, area / cell_volume(C, nb, 1));
     for (int b = 0; b < nq; ++b)
       for (int a = 0; a < nq; ++a) {
-        double xi[3], xn[3], X[3], J[3][3], Ji[3][3], Jn[3][3], Jin[3][3];
+        double xi[3], xn[3], X[3], Ji[3][3], Jn[3][3], Jin[3][3], nv[3], dA;
         xi[d] = s; xi[t1] = C->qp[a]; xi[t2] = C->qp[b];
-        cell_map(C, e, xi, X, J);
-        double det = fabs(inv3(J, Ji));
-        double sg = s ? 1.0 : -1.0;
-        double nv[3] = {sg * Ji[d][0], sg * Ji[d][1], sg * Ji[d][2]};
-        double nr = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-        for (int k = 0; k < 3; ++k) nv[k] /= nr;
-        double wf = det * nr * C->wp[a] * C->wp[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        double wf = dA * C->wp[a] * C->wp[b];
         xn[d] = 1 - s; xn[t1] = xi[t1]; xn[t2] = xi[t2];
         cell_map(C, nb, xn, X, Jn);
         inv3(Jn, Jin);
@@ -1438,6 +1432,36 @@ int orc_cell_map(const orc_params *P, int64_t e, const double *xi, double *X, do
   *detJ = inv3(J, Ji);
   ctx_free(&C);
   return 0;
+}
+
+/* Quadrature points of face f = 2 d + s of cell e with the face rule of the
+ * velocity residual (the larger tangential counts of the two adjacent cells).
+ * Per point, 7 doubles: X[3], n w dA [3] (outward unit normal times weight
+ * times area element) and w dA.  out holds 7 ORC_MAXN^2 doubles; returns the
+ * number of points, negative on bad arguments. */
+int orc_face_points(const orc_params *P, int64_t e, int f, double *out) {
+  ctx C;
+  if (ctx_init(&C, P, NULL)) return -1;
+  if (e < 0 || e >= C.ncell || f < 0 || f > 5) { ctx_free(&C); return -2; }
+  int d = f / 2, s = f % 2;
+  int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  int64_t nb = face_neighbor(&C, e, d, s);
+  const double *q1, *w1, *q2, *w2;
+  int n1, n2;
+  face_rule(&C, e, nb, t1, t2, &q1, &w1, &n1, &q2, &w2, &n2);
+  int np = 0;
+  for (int b = 0; b < n2; ++b)
+    for (int a = 0; a < n1; ++a) {
+      double xi[3], X[3], Ji[3][3], nv[3], dA;
+      xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
+      face_point(&C, e, d, s, xi, X, Ji, nv, &dA);
+      double wf = dA * w1[a] * w2[b];
+      double *o = out + 7 * np++;
+      for (int k = 0; k < 3; ++k) { o[k] = X[k]; o[3 + k] = nv[k] * wf; }
+      o[6] = wf;
+    }
+  ctx_free(&C);
+  return np;
 }
 
 /* Number of OpenMP threads the oracle uses (for reporting). */
