@@ -72,29 +72,57 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
     pts, wts = volume_rule(cfg)
     V = basis_at(cfg, pts)
     eta = vertex_eta(cfg)
-    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
     off = cfg.ncell * 3 * n3
     conds = np.zeros(len(cells))
     todo = range(len(cells)) if only is None else sorted(set(int(k) for k in only))
     for k in todo:
         e = cells[k]
-        ey = (e // cfg.nx) % cfg.ny
-        detJ = hx * (eta[ey + 1] - eta[ey]) * hz
-        w = wts * detJ
-        po, pn = np.asarray(psi_old[k], dtype=float), np.asarray(psi_new[k], dtype=float)
-        on = bool(np.any(pn != 0.0))
-        Phi = np.hstack([V, pn[:, None]]) if on else V           # new local basis at the points
+        w, Phi, uq, on = _l2_cell(cfg, k, u_old, psi_old[k], psi_new[k], V, wts, eta, cells)
         sw = np.sqrt(w)
         A = sw[:, None] * Phi
         conds[k] = np.linalg.cond(A.T @ A)
         for c in range(3):
-            ub = u_old[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
-            ut = u_old[off + 3 * k + c]
-            uq = V @ ub + po * ut                                # u_old at the points
-            x = np.linalg.lstsq(A, sw * uq, rcond=None)[0]
+            x = np.linalg.lstsq(A, sw * uq[c], rcond=None)[0]
             u_new[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = x[:n3]
             u_new[off + 3 * k + c] = x[n3] if on else 0.0
     return (u_new, conds) if return_cond else u_new
+
+
+def _l2_cell(cfg, k, u_old, psi_old_k, psi_new_k, V, wts, eta, cells):
+    """Quadrature weights w (times |det J|), the new local basis Phi at the
+    points, the old velocity uq[c] at the points and the activity of enriched
+    cell k (position in enrichment order)."""
+    n3 = (cfg.k_u + 1) ** 3
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    off = cfg.ncell * 3 * n3
+    e = cells[k]
+    ey = (e // cfg.nx) % cfg.ny
+    detJ = hx * (eta[ey + 1] - eta[ey]) * hz
+    w = wts * detJ
+    po, pn = np.asarray(psi_old_k, dtype=float), np.asarray(psi_new_k, dtype=float)
+    on = bool(np.any(pn != 0.0))
+    Phi = np.hstack([V, pn[:, None]]) if on else V           # new local basis at the points
+    uq = []
+    for c in range(3):
+        ub = u_old[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
+        ut = u_old[off + 3 * k + c]
+        uq.append(V @ ub + po * ut)                          # u_old at the points
+    return w, Phi, uq, on
+
+
+def l2_normal_equation(cfg, k, u_old, psi_old_k, psi_new_k):
+    """Eq. l2 of enriched cell k written as its normal equation A x_c = b_c per
+    component c: A = Phi^T W Phi (the new local mass matrix), b_c = Phi^T W u_old,c,
+    and babs_c = |Phi|^T W |u_old,c| (a bound on the rounding of b_c)."""
+    cells = enriched_cells(cfg)
+    pts, wts = volume_rule(cfg)
+    V = basis_at(cfg, pts)
+    w, Phi, uq, _ = _l2_cell(cfg, k, np.asarray(u_old, dtype=float), psi_old_k, psi_new_k, V, wts,
+                             vertex_eta(cfg), cells)
+    A = Phi.T @ (w[:, None] * Phi)
+    b = [Phi.T @ (w * q) for q in uq]
+    babs = [np.abs(Phi).T @ (w * np.abs(q)) for q in uq]
+    return A, b, babs
 
 
 def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
@@ -115,7 +143,6 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     r = np.asarray(r, dtype=np.float64)
     x = np.zeros_like(r)
     eta = vertex_eta(cfg)
-    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
     off = cfg.ncell * 3 * n3
     enr = {int(e): k for k, e in enumerate(enriched_cells(cfg))}
     pts_e, wts_e = volume_rule(cfg)
@@ -125,16 +152,8 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     M_reg = V_r.T @ (wts_r[:, None] * V_r)
     conds = np.zeros(cfg.ncell)
     for e in (range(cfg.ncell) if cells is None else [int(c) for c in cells]):
-        ey = (e // cfg.nx) % cfg.ny
-        detJ = hx * (eta[ey + 1] - eta[ey]) * hz
         k = enr.get(e)
-        if k is None:
-            M = detJ * M_reg
-        else:
-            ps = np.asarray(psi[k], dtype=float)
-            on = bool(np.any(ps != 0.0))
-            Phi = np.hstack([V_e, ps[:, None]]) if on else V_e
-            M = Phi.T @ ((detJ * wts_e)[:, None] * Phi)
+        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e)
         conds[e] = np.linalg.cond(M)
         for c in range(3):
             rp = r[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
@@ -145,6 +164,33 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
             else:
                 x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = np.linalg.solve(M, rp)
     return (x, conds) if return_cond else x
+
+
+def _mass_block(cfg, e, psi_k, eta, M_reg, V_e, wts_e):
+    """Per-component mass matrix of cell e over its local basis (N_B, plus psi
+    while an enriched cell's enrichment is on), the cell's own rule."""
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    ey = (e // cfg.nx) % cfg.ny
+    detJ = hx * (eta[ey + 1] - eta[ey]) * hz
+    if psi_k is None:
+        return detJ * M_reg
+    ps = np.asarray(psi_k, dtype=float)
+    on = bool(np.any(ps != 0.0))
+    Phi = np.hstack([V_e, ps[:, None]]) if on else V_e
+    return Phi.T @ ((detJ * wts_e)[:, None] * Phi)
+
+
+def mass_block(cfg, e, psi_k=None):
+    """The block of cell e that inverse_mass inverts, per component: (n+1) x (n+1)
+    with n = (k_u+1)^3 in an enriched cell whose enrichment is on (psi_k: psi at
+    the enriched volume rule), n x n otherwise (psi_k None for a cell without
+    enrichment)."""
+    pts_e, wts_e = volume_rule(cfg)
+    V_e = basis_at(cfg, pts_e)
+    pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
+    V_r = basis_at(cfg, pts_r)
+    M_reg = V_r.T @ (wts_r[:, None] * V_r)
+    return _mass_block(cfg, int(e), psi_k, vertex_eta(cfg), M_reg, V_e, wts_e)
 
 
 def _basis_grad_at(cfg, pts, h):
@@ -158,6 +204,46 @@ def _basis_grad_at(cfg, pts, h):
         G[q, :, 1] = np.einsum("m,j,i->mji", vz, dy, vx).reshape(-1) / h[1]
         G[q, :, 2] = np.einsum("m,j,i->mji", dz, vy, vx).reshape(-1) / h[2]
     return G
+
+
+def _projection_block(cfg, e, psi4_k, tau_d_e, eta, rule_e, rule_r):
+    """M_e and D_e of eq. projectionspat over the local basis of cell e (the
+    three components of N_B, plus psi e_c while the enrichment is on)."""
+    n3 = (cfg.k_u + 1) ** 3
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    ey = (e // cfg.nx) % cfg.ny
+    h = (hx, eta[ey + 1] - eta[ey], hz)
+    detJ = h[0] * h[1] * h[2]
+    pts, wts, V = rule_e if psi4_k is not None else rule_r
+    G = _basis_grad_at(cfg, pts, h)
+    w = wts * detJ
+    on = psi4_k is not None and bool(np.any(psi4_k[:, 0] != 0.0))
+    nb = 3 * n3 + (3 if on else 0)
+    # values (npts, 3, nb) and divergences (npts, nb) of the local basis
+    val = np.zeros((len(pts), 3, nb))
+    div = np.zeros((len(pts), nb))
+    for c in range(3):
+        val[:, c, c * n3:(c + 1) * n3] = V
+        div[:, c * n3:(c + 1) * n3] = G[:, :, c]
+        if on:
+            val[:, c, 3 * n3 + c] = psi4_k[:, 0]
+            div[:, 3 * n3 + c] = psi4_k[:, 1 + c]
+    M = np.einsum("q,qci,qcj->ij", w, val, val)
+    D = tau_d_e * np.einsum("q,qi,qj->ij", w, div, div)
+    return M, D, on
+
+
+def projection_block(cfg, e, tau_d_e, psi4_k=None):
+    """(M_e, D_e) of the projection step for cell e: 3 n (+3 while an enriched
+    cell's enrichment is on) square, unknowns ordered as in the velocity
+    layout (components of N_B, then the three enrichment coefficients).
+    psi4_k: psi and grad psi at the enriched volume rule, None for a cell
+    without enrichment."""
+    pts_e, wts_e = volume_rule(cfg)
+    pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
+    M, D, _ = _projection_block(cfg, int(e), psi4_k, tau_d_e, vertex_eta(cfg),
+                                (pts_e, wts_e, basis_at(cfg, pts_e)), (pts_r, wts_r, basis_at(cfg, pts_r)))
+    return M, D
 
 
 def projection_step(cfg, u_hat, g, scale, tau_d, psi4, cells=None):
@@ -178,33 +264,15 @@ def projection_step(cfg, u_hat, g, scale, tau_d, psi4, cells=None):
     g = np.asarray(g, dtype=np.float64)
     x = np.zeros_like(u_hat)
     eta = vertex_eta(cfg)
-    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
     off = cfg.ncell * 3 * n3
     enr = {int(e): k for k, e in enumerate(enriched_cells(cfg))}
     pts_e, wts_e = volume_rule(cfg)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     V_e, V_r = basis_at(cfg, pts_e), basis_at(cfg, pts_r)
     for e in (range(cfg.ncell) if cells is None else (int(c) for c in cells)):
-        ey = (e // cfg.nx) % cfg.ny
-        h = (hx, eta[ey + 1] - eta[ey], hz)
-        detJ = h[0] * h[1] * h[2]
         k = enr.get(e)
-        pts, wts, V = (pts_e, wts_e, V_e) if k is not None else (pts_r, wts_r, V_r)
-        G = _basis_grad_at(cfg, pts, h)
-        w = wts * detJ
-        on = k is not None and bool(np.any(psi4[k][:, 0] != 0.0))
-        nb = 3 * n3 + (3 if on else 0)
-        # values (npts, 3, nb) and divergences (npts, nb) of the local basis
-        val = np.zeros((len(pts), 3, nb))
-        div = np.zeros((len(pts), nb))
-        for c in range(3):
-            val[:, c, c * n3:(c + 1) * n3] = V
-            div[:, c * n3:(c + 1) * n3] = G[:, :, c]
-            if on:
-                val[:, c, 3 * n3 + c] = psi4[k][:, 0]
-                div[:, 3 * n3 + c] = psi4[k][:, 1 + c]
-        M = np.einsum("q,qci,qcj->ij", w, val, val)
-        D = tau_d[e] * np.einsum("q,qi,qj->ij", w, div, div)
+        M, D, on = _projection_block(cfg, e, None if k is None else psi4[k], tau_d[e], eta,
+                                     (pts_e, wts_e, V_e), (pts_r, wts_r, V_r))
         # right-hand side: M u_hat - scale g
         coef = np.concatenate([u_hat[e * 3 * n3:(e + 1) * 3 * n3]] + ([u_hat[off + 3 * k: off + 3 * k + 3]] if on else []))
         rhs = M @ coef - scale * np.concatenate([g[e * 3 * n3:(e + 1) * 3 * n3]] +

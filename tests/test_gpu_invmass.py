@@ -6,7 +6,10 @@ the largest entry.  Enriched cells: the block of the local basis (N_B, psi)
 has condition numbers of 1e6-1e8 where psi is close to a polynomial on the
 cell, so any two correct solvers may differ by about eps cond(M) relative to
 the cell's solution; each enriched cell is held to 64 eps cond(M_cell) of its
-largest entry.
+largest entry.  Beside that forward bound every enriched cell is held to a
+backward error ||M x_gpu - r|| <= 2 n eps (||M|| ||x_gpu|| + ||r||) per
+component (n the block size), M the oracle's block assembled from basis
+values: this bound does not grow with cond(M).
 """
 import numpy as np
 import pytest
@@ -16,6 +19,7 @@ import oracle as O
 from oracle import project as OP
 from paper_1705_08813_amd import DgError, Mesh
 from paper_1705_08813_amd.inputs import PRESETS, MeshConfig, Workload, draw_inputs
+from numerics import backward_error
 
 pytestmark = pytest.mark.gpu
 
@@ -37,11 +41,12 @@ def _log(msg):
     print(msg, flush=True)
 
 
-def _check(cfg, x, ref, conds, cells):
-    n3 = 3 * (cfg.k_u + 1) ** 3
+def _check(cfg, x, ref, conds, cells, r=None, psi=None):
+    n1 = (cfg.k_u + 1) ** 3
+    n3 = 3 * n1
     off = cfg.ncell * n3
     enr = {int(e): k for k, e in enumerate(O.enriched_cells(cfg))}
-    worst = 0.0
+    worst = worst_bwd = 0.0
     for e in cells:
         idx = np.arange(e * n3, (e + 1) * n3)
         k = enr.get(int(e))
@@ -52,6 +57,17 @@ def _check(cfg, x, ref, conds, cells):
         tol = 1e-12 if k is None else max(1e-12, 64 * EPS * conds[e])
         worst = max(worst, err / tol)
         assert err <= tol, (int(e), err, tol)
+        if k is not None and psi is not None:
+            M = OP.mass_block(cfg, e, psi[k])
+            for c in range(3):
+                rows = np.arange((e * 3 + c) * n1, (e * 3 + c + 1) * n1)
+                if M.shape[0] == n1 + 1:
+                    rows = np.append(rows, off + 3 * k + c)
+                eta = backward_error(M, x[rows], r[rows])
+                worst_bwd = max(worst_bwd, eta / EPS)
+                assert eta <= 2 * M.shape[0] * EPS, (int(e), c, eta / EPS)
+    if psi is not None:
+        _log(f"[gpu]   worst backward error {worst_bwd:.1f} eps")
     return worst
 
 
@@ -65,7 +81,7 @@ def test_inverse_mass_matches_oracle(name):
     ref, conds = OP.inverse_mass(cfg, inp["u"], psi, return_cond=True)
     mesh = Mesh(cfg, inp["tau"])
     x = mesh.apply_inverse_mass(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
-    worst = _check(cfg, x, ref, conds, range(cfg.ncell))
+    worst = _check(cfg, x, ref, conds, range(cfg.ncell), inp["u"], psi)
     _log(f"[gpu]   max cond {conds.max():.2e}, worst err/tol {worst:.3f}")
     if name == "k3_switch_off":
         act = O.enrichment_active(cfg, tau=inp["tau"])
@@ -81,18 +97,18 @@ def test_inverse_mass_in_place_and_after_nodal_update():
     mesh = Mesh(cfg, inp["tau"])
     r = torch.tensor(inp["u"], device="cuda")
     x0 = mesh.apply_inverse_mass(r).cpu().numpy()      # fills the cache of the setup psi
-    ref0, conds0 = OP.inverse_mass(cfg, inp["u"], O.psi_volume(cfg, O.enriched_cells(cfg), tau=inp["tau"]),
-                                   return_cond=True)
-    _check(cfg, x0, ref0, conds0, range(cfg.ncell))
+    psi0 = O.psi_volume(cfg, O.enriched_cells(cfg), tau=inp["tau"])
+    ref0, conds0 = OP.inverse_mass(cfg, inp["u"], psi0, return_cond=True)
+    _check(cfg, x0, ref0, conds0, range(cfg.ncell), inp["u"], psi0)
     mesh.update_wall_shear_nodes(torch.tensor(tn, device="cuda"))
     x = mesh.apply_inverse_mass(r)                      # the update invalidates the cache
     y = r.clone()
     mesh.apply_inverse_mass(y, y)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
-    ref, conds = OP.inverse_mass(cfg, inp["u"], O.psi_volume(cfg, O.enriched_cells(cfg), tau_nodes=tn),
-                                 return_cond=True)
-    _check(cfg, x.cpu().numpy(), ref, conds, range(cfg.ncell))
+    psi1 = O.psi_volume(cfg, O.enriched_cells(cfg), tau_nodes=tn)
+    ref, conds = OP.inverse_mass(cfg, inp["u"], psi1, return_cond=True)
+    _check(cfg, x.cpu().numpy(), ref, conds, range(cfg.ncell), inp["u"], psi1)
 
 
 def test_inverse_mass_large_mesh_sampled():
@@ -112,7 +128,7 @@ def test_inverse_mass_large_mesh_sampled():
     ek = [enr[int(e)] for e in cells if int(e) in enr]
     psi[ek] = O.psi_volume(cfg, ecells[ek], tau=tau)
     ref, conds = OP.inverse_mass(cfg, inp["u"], psi, cells=cells, return_cond=True)
-    _check(cfg, x, ref, conds, cells)
+    _check(cfg, x, ref, conds, cells, inp["u"], psi)
 
 
 def test_inverse_mass_rejects_curved_mesh():

@@ -71,7 +71,8 @@ def test_velocity_residual_f64(name):
         assert _rel(re, oe) <= 1e-12, _rel(re, oe)
 
 
-@pytest.mark.parametrize("name", ["tiny", "k4_large_like", "k3_periodic", "curved_k3"])
+@pytest.mark.parametrize("name", ["tiny", "k4_large_like", "k3_periodic", "curved_k3", "k5_curved_rule", "curved_k5",
+                                  "curved_k4_stretched"])
 def test_velocity_residual_f32_bound(name):
     wl = VEL_CASES[name]
     _log(f"[gpu] velocity f32 case={name}")
@@ -131,10 +132,22 @@ def test_poisson_f32_bound(name):
     assert worst <= 1.0
 
 
-def test_large_config_poisson_full_and_velocity_sampled():
+def _enrichment_rows(m, cells):
+    n3 = (m.k_u + 1) ** 3
+    off = m.ncell * 3 * n3
+    rows = []
+    for e in cells:
+        ex, ey, ez = e % m.nx, (e // m.nx) % m.ny, e // (m.nx * m.ny)
+        if ey in (0, m.ny - 1):
+            k = ex + m.nx * ((0 if ey == 0 else 1) + 2 * ez)
+            rows += [off + 3 * k + c for c in range(3)]
+    return np.array(rows, dtype=np.int64)
+
+
+def test_large_config_full_field():
     """64x32x32, tanh 1.8, k=4 / k=3, in the configuration the benchmark times:
-    the whole Poisson output against the oracle, and the velocity residual on
-    a sample of cells (both enriched layers, their neighbours, interior)."""
+    the whole Poisson output and the whole velocity residual (polynomial and
+    enrichment blocks) against the oracle."""
     wl = PRESETS["large"]
     m = wl.mesh
     _log("[gpu] large config: setup")
@@ -144,32 +157,13 @@ def test_large_config_poisson_full_and_velocity_sampled():
     y = mesh.apply_poisson(torch.tensor(inp["p"], device="cuda"))
     torch.cuda.synchronize()
     assert _rel(y.cpu().numpy(), O.poisson_apply(m, inp["p"])) <= 1e-12
-    _log("[gpu] large config: velocity f64")
-    u = torch.tensor(inp["u"], device="cuda")
-    r = mesh.apply_velocity_residual(u).cpu().numpy()
-    rng = np.random.default_rng(5)
-    nx, ny, nz = m.nx, m.ny, m.nz
-    cells = set(rng.integers(0, m.ncell, 200).tolist())
-    for ey in (0, 1, ny - 2, ny - 1):
-        for _ in range(40):
-            cells.add(int(rng.integers(0, nx)) + nx * (ey + ny * int(rng.integers(0, nz))))
-    cells |= {0, nx - 1, m.ncell - 1}
-    cells = np.array(sorted(cells), dtype=np.int64)
-    r_orc = O.velocity_residual(m, inp["u"], inp["tau"], cells=cells)
-    n3 = (m.k_u + 1) ** 3
-    rows = (cells[:, None] * 3 * n3 + np.arange(3 * n3)[None, :]).ravel()
-    assert _rel(r[rows], r_orc[rows]) <= 1e-12
-    # enrichment rows of the sampled enriched cells
-    off = m.ncell * 3 * n3
-    enr_rows = []
-    for e in cells:
-        ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
-        if ey in (0, ny - 1):
-            slot = 0 if ey == 0 else 1
-            k = ex + nx * (slot + 2 * ez)
-            enr_rows += [off + 3 * k + c for c in range(3)]
-    enr_rows = np.array(enr_rows)
-    assert _rel(r[enr_rows], r_orc[enr_rows]) <= 1e-12
+    _log("[gpu] large config: velocity f64, oracle on every cell")
+    r = mesh.apply_velocity_residual(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    r_orc = O.velocity_residual(m, inp["u"], inp["tau"])
+    rp, re = _split(m, r)
+    op, oe = _split(m, r_orc)
+    _log(f"[gpu]   rel poly {_rel(rp, op):.2e} enr {_rel(re, oe):.2e}")
+    assert _rel(rp, op) <= 1e-12 and _rel(re, oe) <= 1e-12
 
 
 def test_repeat_applies_are_bitwise_identical():
@@ -199,36 +193,51 @@ def test_wall_shear_update_matches_fresh_setup():
     assert _rel(r, r_orc) <= 1e-12
 
 
-def test_curved_config_sampled():
+def test_curved_config_full_field():
     """48x24x24 curved channel, k=5 (8 Gauss points), both walls enriched,
-    tau_w ~ U[0.2, 2]: sampled cells against the oracle, FP64."""
+    tau_w ~ U[0.2, 2]: every cell against the oracle, FP64."""
     wl = PRESETS["curved"]
     m = wl.mesh
     _log("[gpu] curved config: setup")
     inp = draw_inputs(wl, want=("u", "tau"))
     mesh = Mesh(m, inp["tau"])
     r = mesh.apply_velocity_residual(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
-    rng = np.random.default_rng(8)
-    nx, ny, nz = m.nx, m.ny, m.nz
+    _log("[gpu] curved config: oracle on every cell")
+    r_orc = O.velocity_residual(m, inp["u"], inp["tau"])
+    rp, re = _split(m, r)
+    op, oe = _split(m, r_orc)
+    _log(f"[gpu]   rel poly {_rel(rp, op):.2e} enr {_rel(re, oe):.2e}")
+    assert _rel(rp, op) <= 1e-12 and _rel(re, oe) <= 1e-12
+
+
+def test_curved_config_f32_bound_sampled():
+    """The FP32 apply the benchmark times on the 48x24x24 curved k=5 mesh:
+    sampled cells (both enriched layers, their neighbours, interior) against
+    the elementwise bound 4 m u32 R_abs, the oracle run on the FP32 roundings."""
+    wl = PRESETS["curved"]
+    m = wl.mesh
+    _log("[gpu] curved config f32: setup")
+    inp = draw_inputs(wl, want=("u", "tau"))
+    u32 = inp["u"].astype(np.float32)
+    u_r = u32.astype(np.float64)
+    mesh = Mesh(m, inp["tau"])
+    r = mesh.apply_velocity_residual(torch.tensor(u32, device="cuda")).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(9)
     cells = set(rng.integers(0, m.ncell, 60).tolist())
-    for ey in (0, 1, ny - 2, ny - 1):
+    for ey in (0, 1, m.ny - 2, m.ny - 1):
         for _ in range(15):
-            cells.add(int(rng.integers(0, nx)) + nx * (ey + ny * int(rng.integers(0, nz))))
+            cells.add(int(rng.integers(0, m.nx)) + m.nx * (ey + m.ny * int(rng.integers(0, m.nz))))
     cells = np.array(sorted(cells), dtype=np.int64)
-    _log(f"[gpu] curved config: oracle on {cells.size} cells")
-    r_orc = O.velocity_residual(m, inp["u"], inp["tau"], cells=cells)
+    _log(f"[gpu] curved config f32: oracle on {cells.size} cells")
+    r_orc = O.velocity_residual(m, u_r, inp["tau"], cells=cells)
+    r_abs = O.velocity_residual(m, u_r, inp["tau"], cells=cells, absmode=True)
     n3 = (m.k_u + 1) ** 3
-    rows = (cells[:, None] * 3 * n3 + np.arange(3 * n3)[None, :]).ravel()
-    assert _rel(r[rows], r_orc[rows]) <= 1e-12
-    off = m.ncell * 3 * n3
-    enr_rows = []
-    for e in cells:
-        ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
-        if ey in (0, ny - 1):
-            k = ex + nx * ((0 if ey == 0 else 1) + 2 * ez)
-            enr_rows += [off + 3 * k + c for c in range(3)]
-    enr_rows = np.array(enr_rows)
-    assert _rel(r[enr_rows], r_orc[enr_rows]) <= 1e-12
+    rows = np.concatenate([(cells[:, None] * 3 * n3 + np.arange(3 * n3)[None, :]).ravel(),
+                           _enrichment_rows(m, cells)])
+    mq = 3 * (m.nq_u + m.k_u + 1) + 40
+    worst = float((np.abs(r[rows] - r_orc[rows]) / (4 * mq * U32 * r_abs[rows] + 1e-30)).max())
+    _log(f"[gpu]   max rel err {_rel(r[rows], r_orc[rows]):.3e}, max err/bound {worst:.3f}")
+    assert worst <= 1.0
 
 
 # van Driest's enrichment (Sec. 3.2, eq. psi; Appendix A evaluation on the GPU,

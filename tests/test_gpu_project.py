@@ -10,7 +10,11 @@ weighted least-squares problem (SVD), the kernel by its closed form with
 r = psi - P psi formed pointwise; both lose about eps sqrt(cond(M)) ~ 1e-13
 relative when psi is close to a polynomial on the cell (cond(M) ~ 1e7 at the
 y+ ranges used here), and the enrichment coefficient is divided by (r, r),
-which amplifies that by up to another sqrt(cond(M)): PTOL = 1e-10.
+which amplifies that by up to another sqrt(cond(M)): PTOL = 1e-10.  Every
+projected enriched cell is also held to the backward error of the normal
+equation of eq. l2, ||M x_gpu - b|| <= 2 n eps (||M|| ||x_gpu|| + |Phi|^T W |u_old|)
+per component, M = Phi^T W Phi and b = Phi^T W u_old from the oracle's basis
+values: a bound that does not grow with cond(M).
 """
 import numpy as np
 import pytest
@@ -20,6 +24,7 @@ import oracle as O
 from oracle import project as OP
 from paper_1705_08813_amd import DgError, Mesh
 from paper_1705_08813_amd.inputs import PRESETS, MeshConfig, Workload, draw_inputs
+from numerics import EPS, backward_error
 
 pytestmark = pytest.mark.gpu
 
@@ -117,7 +122,27 @@ def _project_case(cfg, inp, tn_new=None, tau_new=None, tn_old=None):
     cells = O.enriched_cells(cfg)
     ps0 = O.psi_volume(cfg, cells, tau=None if tn_old is not None else inp["tau"], tau_nodes=tn_old)
     ps1 = O.psi_volume(cfg, cells, tau=tau_new, tau_nodes=tn_new)
-    return OP.project(cfg, inp["u"], ps0, ps1, return_cond=True)
+    ref, cond = OP.project(cfg, inp["u"], ps0, ps1, return_cond=True)
+    return ref, cond, ps0, ps1
+
+
+def _check_backward(cfg, u_old, u_new, ps0, ps1, ks):
+    """Backward error of eq. l2's normal equation in the enriched cells at positions ks."""
+    n1 = (cfg.k_u + 1) ** 3
+    off = cfg.ncell * 3 * n1
+    cells = O.enriched_cells(cfg)
+    worst = 0.0
+    for k in ks:
+        e = int(cells[k])
+        A, b, babs = OP.l2_normal_equation(cfg, k, u_old, ps0[k], ps1[k])
+        for c in range(3):
+            rows = np.arange((e * 3 + c) * n1, (e * 3 + c + 1) * n1)
+            if A.shape[0] == n1 + 1:
+                rows = np.append(rows, off + 3 * k + c)
+            eta = backward_error(A, u_new[rows], b[c], babs[c])
+            worst = max(worst, eta / EPS)
+            assert eta <= 2 * A.shape[0] * EPS, (k, c, eta / EPS)
+    _log(f"[gpu]   worst backward error {worst:.1f} eps")
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -146,10 +171,11 @@ def test_projection_matches_oracle(name, mode):
         mesh.update_wall_shear_nodes(torch.tensor(tn1, device="cuda"))
     u = torch.tensor(inp["u"], device="cuda")
     un = mesh.project_velocity(u).cpu().numpy()
-    ref, cond = _project_case(cfg, inp, tn_new=tn1, tau_new=tau1, tn_old=tn0)
+    ref, cond, ps0, ps1 = _project_case(cfg, inp, tn_new=tn1, tau_new=tau1, tn_old=tn0)
     err = _rel(un, ref)
     _log(f"[gpu]   max cond(M) {cond.max():.2e}  rel err {err:.2e}")
     assert err <= PTOL
+    _check_backward(cfg, inp["u"], un, ps0, ps1, range(len(O.enriched_cells(cfg))))
     if mode == "switching":
         a0 = O.enrichment_active(cfg, tau_nodes=tn0)
         a1 = O.enrichment_active(cfg, tau_nodes=tn1)
@@ -211,6 +237,7 @@ def test_large_mesh_projection_sampled():
     idx = np.concatenate([np.arange(e * n3, (e + 1) * n3) for e in cells[pick]] +
                          [(off + 3 * pick[:, None] + np.arange(3)[None, :]).ravel()])
     assert _rel(un[idx], ref[idx]) <= PTOL * np.abs(inp["u"]).max() / max(np.abs(ref[idx]).max(), 1e-300)
+    _check_backward(cfg, inp["u"], un, ps0, ps1, pick)
 
 
 def test_projection_rejects_bad_arguments():

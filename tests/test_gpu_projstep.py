@@ -5,7 +5,10 @@ Per cell, ||x_gpu - x_oracle||_inf <= tol ||x_oracle||_inf with tol = 1e-11 in
 cells without enrichment (both sides are direct solves; the kernel's passes
 through an orthogonal eigenbasis of the whitened block, accurate to about
 1e-13) and max(1e-11, 64 eps cond(M_cell)) in enriched cells, whose mass
-blocks have condition numbers up to 1e8 (as for the inverse mass).
+blocks have condition numbers up to 1e8 (as for the inverse mass).  Every
+enriched cell is also held to a backward error that does not grow with the
+conditioning: ||(M+D) x_gpu - b|| <= 2 n eps (||M+D|| ||x_gpu|| + ||M|| ||u^|| +
+s ||g||) with b = M u^ - s g and M, D the oracle's blocks from basis values.
 """
 import numpy as np
 import pytest
@@ -15,6 +18,7 @@ import oracle as O
 from oracle import project as OP
 from paper_1705_08813_amd import DgError, Mesh
 from paper_1705_08813_amd.inputs import PRESETS, MeshConfig, Workload, draw_inputs
+from numerics import backward_error
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +29,10 @@ CASES = {
     "k4": MeshConfig(nx=3, ny=4, nz=2, gamma=1.2, k_u=4, k_p=3, nq_u=7, nq_p=4, nq_wn=8, nu=1.0 / 1000),
     "k2": MeshConfig(nx=3, ny=4, nz=2, gamma=1.3, k_u=2, k_p=1, nq_u=4, nq_p=2, nq_wn=8, nu=1.0 / 800),
     "k5": MeshConfig(nx=2, ny=3, nz=2, gamma=0.8, k_u=5, k_p=4, nq_u=8, nq_p=5, nq_wn=8, nu=1.0 / 600),
+    # 9 cells per layer: one full and one partial 8-cell tile at k = 5
+    "k5_wide": MeshConfig(nx=3, ny=3, nz=3, gamma=0.8, k_u=5, k_p=4, nq_u=8, nq_p=5, nq_wn=8, nu=1.0 / 600),
+    # 20 cells per layer: one full and one partial 16-cell matrix-core tile at k = 3
+    "k3_wide": MeshConfig(nx=5, ny=3, nz=4, gamma=1.0, k_u=3, k_p=2, nq_u=5, nq_p=3, nq_wn=8, nu=1.0 / 400),
     "k3_one_sided": MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=3, k_p=2, nq_u=5, nq_p=3, nq_wn=8, nu=1.0 / 400,
                                enrich_upper=0),
     "k3_two_layers": MeshConfig(nx=3, ny=2, nz=2, gamma=1.0, k_u=3, k_p=2, nq_u=5, nq_p=3, nq_wn=8, nu=1.0 / 400),
@@ -50,14 +58,16 @@ def test_projection_step_matches_oracle(name):
     mesh = Mesh(cfg, inp["tau"])
     x = mesh.projection_step(torch.tensor(tau_d, device="cuda"), torch.tensor(inp["u"], device="cuda"),
                              torch.tensor(g, device="cuda"), 0.7).cpu().numpy()
-    _check(cfg, x, ref, conds, range(cfg.ncell))
+    _check(cfg, x, ref, conds, range(cfg.ncell), (inp["u"], g, 0.7, tau_d, psi4))
 
 
-def _check(cfg, x, ref, conds, check_cells):
+def _check(cfg, x, ref, conds, check_cells, bwd=None):
+    """bwd: (u_hat, g, scale, tau_d, psi4) for the backward-error check of the
+    enriched cells."""
     n3 = 3 * (cfg.k_u + 1) ** 3
     off = cfg.ncell * n3
     enr = {int(e): k for k, e in enumerate(O.enriched_cells(cfg))}
-    worst = 0.0
+    worst = worst_bwd = 0.0
     for e in check_cells:
         e = int(e)
         idx = np.arange(e * n3, (e + 1) * n3)
@@ -68,7 +78,17 @@ def _check(cfg, x, ref, conds, check_cells):
         tol = 1e-11 if k is None else max(1e-11, 64 * EPS * conds[e])
         worst = max(worst, err / tol)
         assert err <= tol, (e, err, tol)
-    print(f"[gpu]   worst err/tol {worst:.3f}", flush=True)
+        if k is not None and bwd is not None:
+            u_hat, g, scale, tau_d, psi4 = bwd
+            M, D = OP.projection_block(cfg, e, tau_d[e], psi4[k])
+            rows = idx if M.shape[0] == idx.size else idx[:n3]
+            b = M @ u_hat[rows] - scale * g[rows]
+            babs = np.abs(M) @ np.abs(u_hat[rows]) + abs(scale) * np.abs(g[rows])
+            eta = backward_error(M + D, x[rows], b, babs)
+            worst_bwd = max(worst_bwd, eta / EPS)
+            assert eta <= 2 * M.shape[0] * EPS, (e, eta / EPS)
+    print(f"[gpu]   worst err/tol {worst:.3f}" + (f", worst backward error {worst_bwd:.1f} eps" if bwd else ""),
+          flush=True)
 
 
 def test_projection_step_large_mesh_sampled():
@@ -100,7 +120,7 @@ def test_projection_step_large_mesh_sampled():
     psi4[ek] = O.psi_volume4(cfg, ecells[ek], tau=tau)
     ref = OP.projection_step(cfg, inp["u"], g, 1.3, tau_d, psi4, cells=cells)
     _, conds = OP.inverse_mass(cfg, inp["u"], psi4[..., 0], cells=cells, return_cond=True)
-    _check(cfg, x, ref, conds, cells)
+    _check(cfg, x, ref, conds, cells, (inp["u"], g, 1.3, tau_d, psi4))
 
 
 def test_projection_step_rejects_bad_arguments():
@@ -159,7 +179,7 @@ def test_projection_step_follows_wall_shear_update():
     psi4 = O.psi_volume4(cfg, cells, tau=tau2)
     ref = OP.projection_step(cfg, inp["u"], g, 0.7, tau_d, psi4)
     _, conds = OP.inverse_mass(cfg, inp["u"], psi4[..., 0], return_cond=True)
-    _check(cfg, x, ref, conds, range(cfg.ncell))
+    _check(cfg, x, ref, conds, range(cfg.ncell), (inp["u"], g, 0.7, tau_d, psi4))
 
 
 def test_projection_step_is_repeatable():
