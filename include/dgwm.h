@@ -19,8 +19,10 @@
  *  - The library performs no device allocation: every device buffer,
  *    including the mesh tables and solver work vectors, lives in workspace
  *    that the caller allocates (e.g. a torch uint8 tensor) and keeps alive
- *    until dg_destroy_mesh / the end of the call that uses it.  The mesh
- *    handle holds one small pinned host buffer (freed by dg_destroy_mesh).
+ *    until dg_destroy_mesh / the end of the call that uses it; the one
+ *    exception is the built-in per-GPU array of dg_solve_poisson_noalloc.
+ *    The mesh handle holds one small pinned host buffer and one event (freed
+ *    by dg_destroy_mesh).
  *  - Calls on different mesh handles may run concurrently from different
  *    threads; two solves on one handle must not overlap (the handle caches
  *    eigenvalue estimates and stages the solver's scalars), and a wall-shear
@@ -381,6 +383,27 @@ int64_t dg_solve_workspace_bytes_for(const dg_mesh_params* params, const dg_solv
  *   DG_ERR_NONFINITE on NaN/Inf. */
 int dg_solve_poisson(const dg_mesh* mesh, const dg_solve_params* sp, const double* b, double* x, void* workspace,
                      size_t ws_bytes, dg_solve_stats* stats, void* stream);
+
+/* Bytes of solver workspace dg_solve_poisson_noalloc holds per GPU (64 MiB:
+ * Poisson meshes up to about 550,000 unknowns, e.g. 16^3 cells at k_p = 4). */
+#define DG_NOALLOC_SOLVE_MAX_BYTES ((size_t)64 << 20)
+
+/* dg_solve_poisson without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same solve, same arguments and results
+ * as dg_solve_poisson (bit for bit on the same inputs); the solver's work
+ * vectors and partial sums live in a device array of
+ * DG_NOALLOC_SOLVE_MAX_BYTES built into the library, one per GPU, held until
+ * the process ends.  The call allocates nothing (no hipMalloc / hipFree or
+ * allocating library routine); its first call on a device resolves that
+ * device's array address once.  Every call on one GPU shares its array and
+ * leaves its last contents there (each solve writes every byte it reads), so
+ * calls that overlap on one GPU, from any thread or stream, race: serialise
+ * them.  The mesh must live on the current device.
+ *   Errors: as dg_solve_poisson, plus DG_ERR_WORKSPACE when
+ *   dg_solve_workspace_bytes(mesh) exceeds DG_NOALLOC_SOLVE_MAX_BYTES. */
+int dg_solve_poisson_noalloc(const dg_mesh* mesh, const dg_solve_params* sp, const double* b, double* x,
+                             dg_solve_stats* stats, void* stream);
 
 /* ---------------------------------------------------------------- misc --- */
 

@@ -252,6 +252,23 @@ class Mesh:
                                                workspace.numel(), ctypes.byref(st), _stream_ptr(stream)))
         return x, st
 
+    def solve_poisson_noalloc(self, b, x=None, sp=None, stream=None):
+        """dg_solve_poisson_noalloc: the solve with the library's built-in
+        per-GPU workspace (no workspace argument, nothing allocated)."""
+        import torch
+        if sp is None:
+            sp = self.solve_params()
+        if b.dtype != torch.float64:
+            raise ValueError("b must be float64")
+        self._check_vec(b, self.n_p, "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        self._check_vec(x, self.n_p, "x")
+        st = SolveStats()
+        _lib.check(_lib.lib().dg_solve_poisson_noalloc(self.handle, ctypes.byref(sp), _dptr(b), _dptr(x),
+                                                       ctypes.byref(st), _stream_ptr(stream)))
+        return x, st
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.lib().dg_destroy_mesh(self.handle)

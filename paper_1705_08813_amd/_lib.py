@@ -81,6 +81,8 @@ _SIGS = {
     "dg_solve_workspace_bytes_for": (ctypes.c_int64, [ctypes.POINTER(MeshParams), ctypes.POINTER(SolveParams)]),
     "dg_solve_poisson": (ctypes.c_int, [_VP, ctypes.POINTER(SolveParams), _VP, _VP, _VP, ctypes.c_size_t,
                                         ctypes.POINTER(SolveStats), _VP]),
+    "dg_solve_poisson_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(SolveParams), _VP, _VP,
+                                                ctypes.POINTER(SolveStats), _VP]),
     "dg_last_error": (ctypes.c_char_p, []),
     "dg_build_info": (ctypes.c_char_p, []),
 }

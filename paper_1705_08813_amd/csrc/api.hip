@@ -367,6 +367,10 @@ int dg_setup_mesh(const dg_mesh_params* params, const double* tau_w_host, void* 
     (void)hipGetLastError();
     m->host_sc = nullptr;
   }
+  if (m->host_sc && hipEventCreateWithFlags(&m->host_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    m->host_ev = nullptr;
+  }
   *out = m;
   return DG_OK;
 }
@@ -486,6 +490,7 @@ int64_t dg_num_enriched(const dg_mesh* m) {
 }
 
 void dg_destroy_mesh(dg_mesh* m) {
+  if (m && m->host_ev) (void)hipEventDestroy(m->host_ev);
   if (m && m->host_sc) (void)hipHostFree(m->host_sc);
   delete m;
 }

@@ -140,6 +140,7 @@ struct dg_mesh {
   int psi_pts;            // points per enriched cell in the psi tables
   double hx, hz;
   double* host_sc = nullptr;  // pinned host slots for scalars the solver reads back (nullptr: none)
+  hipEvent_t host_ev = nullptr;  // marks the copy into host_sc (nullptr: the solver reads synchronously)
   // device
   double* eta;            // ny+1 wall-normal vertex coordinates
   double* tab_u;          // velocity tables (np_u, nq_u, nq_wn)

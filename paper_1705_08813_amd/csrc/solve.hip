@@ -19,6 +19,8 @@
 // The null space (constants) is handled by projecting b and x to zero mean.
 #include <algorithm>
 #include <chrono>
+#include <mutex>
+#include <string>
 #include <cmath>
 #include <vector>
 
@@ -255,8 +257,7 @@ __global__ void k_hash_fill(double* __restrict__ a, int64_t n) {
 }
 
 // largest eigenvalue of a symmetric tridiagonal matrix (Sturm bisection)
-double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
-  const int n = (int)a.size();
+double tridiag_max_eig(const double* a, const double* b, int n) {
   double lo = 1e300, hi = -1e300;
   for (int i = 0; i < n; ++i) {
     const double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < n ? std::fabs(b[i]) : 0);
@@ -500,21 +501,21 @@ int Solver::lanczos(int l, double* out) {
   if ((rc = check_hip(hipMemcpyAsync(h, RZ, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s), "lanczos copy")))
     return rc;
   if ((rc = check_hip(hipStreamSynchronize(s), "lanczos"))) return rc;
-  std::vector<double> al, be;
+  double al[K], be[K], diag[K], off[K];
+  int kk = 0;
   for (int k = 0; k < K; ++k) {
     const double rz = h[k], pq = h[K + k];
     if (!(rz > 0) || !(pq > 0) || !std::isfinite(rz) || !std::isfinite(pq)) break;
-    if (k > 0) be.push_back(rz / h[k - 1]);
-    al.push_back(rz / pq);
+    if (k > 0) be[k - 1] = rz / h[k - 1];
+    al[k] = rz / pq;
+    kk = k + 1;
   }
-  const int kk = (int)al.size();
   if (kk < 1) return set_error(DG_ERR_NONFINITE, "eigenvalue estimate failed");
-  std::vector<double> diag(kk), off(kk > 1 ? kk - 1 : 0);
   for (int j = 0; j < kk; ++j) {
     diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
     if (j + 1 < kk) off[j] = std::sqrt(be[j]) / al[j];
   }
-  *out = tridiag_max_eig(diag, off);
+  *out = tridiag_max_eig(diag, off, kk);
   return DG_OK;
 }
 
@@ -544,14 +545,13 @@ size_t solve_bytes_mesh(const dg_mesh& m) {
 }
 }  // namespace dgwm
 
-extern "C" {
+namespace {
 
-int64_t dg_solve_workspace_bytes(const dg_mesh* m, const dg_solve_params* sp) {
-  if (!m || !sp) return set_error(DG_ERR_ARG, "mesh/params is NULL");
-  return (int64_t)solve_bytes(m);
-}
-
-int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* b, double* x, void* ws,
+// The solve on a workspace that holds at least solve_bytes(m) bytes; every
+// byte of it is written before it is read, so its previous contents do not
+// matter.  Allocates nothing (the pinned norm slot and its event belong to
+// the mesh handle).
+int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* b, double* x, void* ws,
                      size_t ws_bytes, dg_solve_stats* st, void* stream) {
   const auto t_start = std::chrono::steady_clock::now();
   if (!m || !sp || !b || !x || !ws) return set_error(DG_ERR_ARG, "mesh/params/b/x/workspace is NULL");
@@ -696,14 +696,7 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
   // next preconditioner can be queued behind the copy and runs while the
   // host waits for the norm (it touches neither x, r nor p)
   double* hsc = m->host_sc;
-  hipEvent_t ev = nullptr;
-  if (hsc && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
-  struct EvGuard {
-    hipEvent_t e;
-    ~EvGuard() {
-      if (e) (void)hipEventDestroy(e);
-    }
-  } ev_guard{ev};
+  hipEvent_t ev = hsc ? m->host_ev : nullptr;
 
   double rn = true_residual();
   if (!std::isfinite(rn)) return set_error(DG_ERR_NONFINITE, "non-finite residual");
@@ -766,6 +759,67 @@ int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* 
 #undef DG_TRY
   if (!converged) return set_error(DG_ERR_NOT_CONVERGED, "iteration cap reached");
   return DG_OK;
+}
+
+}  // namespace
+
+// Solve workspace of dg_solve_poisson_noalloc: one copy per GPU, held until
+// the process ends.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[DG_NOALLOC_SOLVE_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (nullptr: not resolved yet)
+
+// Address of `scratch` on the current device, resolved once per device with
+// that device current.
+int scratch_address(void** out) {
+  int dev = -1;
+  if (int rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(DG_ERR_ARG, "device index outside the supported range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (int rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) return rc;
+    if (!p) return set_error(DG_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t dg_solve_workspace_bytes(const dg_mesh* m, const dg_solve_params* sp) {
+  if (!m || !sp) return set_error(DG_ERR_ARG, "mesh/params is NULL");
+  return (int64_t)solve_bytes(m);
+}
+
+int dg_solve_poisson(const dg_mesh* m, const dg_solve_params* sp, const double* b, double* x, void* ws,
+                     size_t ws_bytes, dg_solve_stats* st, void* stream) {
+  return solve_poisson_ws(m, sp, b, x, ws, ws_bytes, st, stream);
+}
+
+int dg_solve_poisson_noalloc(const dg_mesh* m, const dg_solve_params* sp, const double* b, double* x,
+                             dg_solve_stats* st, void* stream) {
+  if (!m || !sp || !b || !x) return set_error(DG_ERR_ARG, "mesh/params/b/x is NULL");
+  const size_t need = solve_bytes(m);
+  if (need > (size_t)DG_NOALLOC_SOLVE_MAX_BYTES)
+    return set_error(DG_ERR_WORKSPACE, "the solve needs more workspace than the built-in scratch holds (" +
+                                           std::to_string(need) + " > " +
+                                           std::to_string((size_t)DG_NOALLOC_SOLVE_MAX_BYTES) +
+                                           " bytes): use dg_solve_poisson with a caller workspace");
+  int dev = -1;
+  if (int rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
+  if (dev != m->device) return set_error(DG_ERR_ARG, "the mesh lives on another device than the current one");
+  void* ws = nullptr;
+  if (int rc = scratch_address(&ws)) return rc;
+  return solve_poisson_ws(m, sp, b, x, ws, (size_t)DG_NOALLOC_SOLVE_MAX_BYTES, st, stream);
 }
 
 }  // extern "C"
