@@ -119,11 +119,14 @@ struct Lobatto {
 
 // Tables of the NP-node Lobatto basis against the NQ-point Gauss rule:
 //   S[q][i] = N_i(g_q), Sd[q][i] = N_i'(g_q), D[q][r] = L_r'(g_q) (Lagrange
-//   through the Gauss points), w, g, nd0[i] = N_i'(0), nd1[i] = N_i'(1).
+//   through the Gauss points), w, g, nd0[i] = N_i'(0), nd1[i] = N_i'(1),
+//   E0[q] = L_q(0), E1[q] = L_q(1): the values at the two ends of the
+//   polynomial through NQ samples at the Gauss points (exact extrapolation of
+//   any polynomial of degree < NQ to xi = 0 and xi = 1).
 template <int NP, int NQ>
 struct Tab {
-  double S[NQ][NP], Sd[NQ][NP], D[NQ][NQ], w[NQ], g[NQ], nd0[NP], nd1[NP];
-  constexpr Tab() : S{}, Sd{}, D{}, w{}, g{}, nd0{}, nd1{} {
+  double S[NQ][NP], Sd[NQ][NP], D[NQ][NQ], w[NQ], g[NQ], nd0[NP], nd1[NP], E0[NQ], E1[NQ];
+  constexpr Tab() : S{}, Sd{}, D{}, w{}, g{}, nd0{}, nd1{}, E0{}, E1{} {
     const Gauss<NQ> G;
     const Lobatto<NP> L;
     for (int q = 0; q < NQ; ++q) {
@@ -146,6 +149,11 @@ struct Tab {
     for (int i = 0; i < NP; ++i) nd0[i] = d[i];
     lagrange(L.x, 1.0, v, d);
     for (int i = 0; i < NP; ++i) nd1[i] = d[i];
+    double e[NQ] = {}, de[NQ] = {};
+    lagrange(g, 0.0, e, de);
+    for (int q = 0; q < NQ; ++q) E0[q] = e[q];
+    lagrange(g, 1.0, e, de);
+    for (int q = 0; q < NQ; ++q) E1[q] = e[q];
   }
 };
 

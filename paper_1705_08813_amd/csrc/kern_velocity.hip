@@ -797,11 +797,505 @@ __device__ __forceinline__ void vel_faces_dir_curved(const MeshDev& M, int64_t e
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Affine (box) cells: face terms folded into the volume quadrature.
+//
+// Along every direction the velocity, its collocation gradient and every
+// test function N_B, grad N_B restricted to a line of Gauss points are
+// polynomials of degree <= k < n_q, so their values at the two faces are the
+// exact extrapolations  f(0) = sum_q E0[q] f(g_q),  f(1) = sum_q E1[q] f(g_q).
+// Hence
+//   - the cell's own traces at the face Gauss points come from the volume
+//     values and gradients at the Gauss points (one contraction along the
+//     face normal), and
+//   - the face test integrals  sum_f w_f (N_B fv + grad N_B : F_g)  equal
+//     sum_q N_B(q) V(q) + grad N_B(q) : G_f(q)  with V and G_f the face fluxes
+//     spread along the normal lines with E0 / E1, so they are added to the
+//     volume flux G (and a value-test field V) before the transposed sweeps.
+// Only the neighbour's traces still need a 2-D interpolation of its node
+// layers.  With n = +-e_D the flux needs per side only u_c and the normal
+// column of the symmetric gradient, s_c = (grad u + grad u^T)_{cD}, and
+// F_g = -theta nu sym([u] (x) n) has the three distinct entries F_g[c][D] =
+// F_g[D][c]: six fields per face point in both directions.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ constexpr int aff_q1(int D, int NQ, int NQY) { return D == 0 ? NQY : NQ; }
+__host__ __device__ constexpr int aff_q2(int D, int NQ, int NQY) { return D == 2 ? NQY : NQ; }
+__host__ __device__ constexpr int aff_qd(int D, int NQ, int NQY) { return D == 1 ? NQY : NQ; }
+constexpr int kAffFields = 6;
+// start of face f = 2 D + s in the face-field array [face][field 0..5][point]
+__host__ __device__ constexpr int aff_foff(int f, int NQ, int NQY) {
+  int o = 0;
+  for (int g = 0; g < f; ++g) o += kAffFields * aff_q1(g / 2, NQ, NQY) * aff_q2(g / 2, NQ, NQY);
+  return o;
+}
+
+template <typename T, int NP, int NQ, int NQY>
+struct AffShape {
+  static constexpr int NP2 = NP * NP, NP3 = NP * NP * NP;
+  static constexpr int NPTS = NQ * NQY * NQ;
+  static constexpr int NL = 6 * 3 * 2 * NP2;             // neighbour layers [face][c][val|d_n][NP2]
+  static constexpr int TA = 3 * NQ * NP * NP;             // interpolation temporaries (in the gradient region)
+  static constexpr int TB = 3 * NQ * NQY * NP;
+  // the neighbour layers go behind the temporaries when they fit, so that they
+  // are stored in the phase of the last interpolation sweep
+  static constexpr bool NL_EARLY = TA + TB + NL <= 9 * NPTS;
+  static constexpr int VOL = 12 * NPTS;                   // u [c][pt], then grad u [c][d][pt]
+  static constexpr int FLR = aff_foff(6, NQ, NQY);        // face fields
+  static constexpr int FL = FLR > TB ? FLR : TB;          // (also the integration temporary)
+  static constexpr int BYTES = (int)sizeof(T) * (3 * NP3 + VOL + FL);
+  static constexpr bool fits = NL <= 9 * NPTS && BYTES <= 80 * 1024;
+};
+
+__device__ __forceinline__ int rotate_tid(int tofs) {
+  const int t = (int)threadIdx.x;
+  return t >= tofs ? t - tofs : t + 256 - tofs;
+}
+
+// Neighbour traces on the two faces of direction D at the face Gauss points,
+// from the neighbour's node layers (value, physical normal derivative):
+// fields 0-2 u_c, 3-5 s_c = d_D u_c + d_c u_D.  One thread per (face, field,
+// q1): rows along t1 (per-lane rows of S1, S1' from LDS), then the t2 sweep
+// with literal coefficients.  Items come in three kinds, in this order:
+// u_c and s_D = 2 d_D u_D (one row sweep); s_T1 (adds the S1' row of u_D);
+// s_T2 (adds the S2' sweep of the S1 rows of u_D).
+template <typename T, int NP, int NQ, int NQY, int D>
+__device__ __forceinline__ void aff_nb_traces(const T* s_nl, const T* s_tab, T* FL, bool wall0, bool wall1, T iht1,
+                                              T iht2, int tofs) {
+  constexpr int T1 = D == 0 ? 1 : 0;
+  constexpr int T2 = D == 2 ? 1 : 2;
+  constexpr int Q1 = aff_q1(D, NQ, NQY), Q2 = aff_q2(D, NQ, NQY), FP = Q1 * Q2;
+  constexpr int NP2 = NP * NP;
+  using TL = FaceTab<NP, NQ, NQY>;
+  constexpr auto& tb2 = ct::tab<NP, Q2>;
+  constexpr int N0 = 2 * 4 * Q1, N1 = N0 + 2 * Q1, N = N1 + 2 * Q1;
+  constexpr int SROW = T1 == 1 ? TL::Sy : TL::Sq, SDROW = T1 == 1 ? TL::Sdy : TL::Sdq;
+  for (int t = rotate_tid(tofs); t < N; t += 256) {
+    const int kind = t < N0 ? 0 : (t < N1 ? 1 : 2);
+    const int tt = kind == 0 ? t : (kind == 1 ? t - N0 : t - N1);
+    const int q1 = tt % Q1;
+    const int r = tt / Q1;
+    const int j = kind == 0 ? (r & 3) : 0;
+    const int s = kind == 0 ? (r >> 2) : r;
+    if (s ? wall1 : wall0) continue;
+    const T* lay = s_nl + (2 * D + s) * 3 * 2 * NP2;  // [c][val|d_n][NP2] of this face
+    T m1[NP];
+#pragma unroll
+    for (int i1 = 0; i1 < NP; ++i1) m1[i1] = s_tab[SROW + q1 * NP + i1];
+    // first row sweep: u_c (j < 3), s_D (j == 3), or the normal-derivative part of s_T1 / s_T2
+    const int c = kind == 0 ? (j < 3 ? j : D) : (kind == 1 ? T1 : T2);
+    const T* la = lay + (c * 2 + (kind == 0 && j < 3 ? 0 : 1)) * NP2;
+    const T sc = (kind == 0 && j == 3) ? T(2) : T(1);
+    T a[NP];
+#pragma unroll
+    for (int i2 = 0; i2 < NP; ++i2) {
+      T acc = 0;
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) acc += m1[i1] * la[i1 + NP * i2];
+      a[i2] = acc * sc;
+    }
+    const int fo = kind == 0 ? (j < 3 ? j : 3 + D) : (kind == 1 ? 3 + T1 : 3 + T2);
+    T* o = FL + aff_foff(2 * D + s, NQ, NQY) + fo * FP + q1;
+    const T* lD = lay + (D * 2 + 0) * NP2;  // value layer of u_D
+    if (kind == 1) {
+      // + d_T1 u_D: S1' rows of the value layer of u_D
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) m1[i1] = s_tab[SDROW + q1 * NP + i1];
+#pragma unroll
+      for (int i2 = 0; i2 < NP; ++i2) {
+        T acc = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < NP; ++i1) acc += m1[i1] * lD[i1 + NP * i2];
+        a[i2] += acc * iht1;
+      }
+    }
+    if (kind == 2) {
+      // + d_T2 u_D: S2' sweep of the S1 rows of the value layer of u_D
+      T b[NP];
+#pragma unroll
+      for (int i2 = 0; i2 < NP; ++i2) {
+        T acc = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < NP; ++i1) acc += m1[i1] * lD[i1 + NP * i2];
+        b[i2] = acc * iht2;
+      }
+#pragma unroll
+      for (int q2 = 0; q2 < Q2; ++q2) {
+        T acc = 0;
+#pragma unroll
+        for (int i2 = 0; i2 < NP; ++i2) acc += T(tb2.S[q2][i2]) * a[i2] + T(tb2.Sd[q2][i2]) * b[i2];
+        o[q2 * Q1] = acc;
+      }
+    } else {
+#pragma unroll
+      for (int q2 = 0; q2 < Q2; ++q2) {
+        T acc = 0;
+#pragma unroll
+        for (int i2 = 0; i2 < NP; ++i2) acc += T(tb2.S[q2][i2]) * a[i2];
+        o[q2 * Q1] = acc;
+      }
+    }
+  }
+}
+
+// Numerical flux on face f = 2 D + S at every face Gauss point: own traces
+// extrapolated from the volume values and gradients along the normal line,
+// neighbour traces from FL (or the mirror state on a wall), then
+// fv = {{u (x) u}} n + Lambda/2 [u] - {{2 nu eps(u)}} n + tau nu [u] and
+// F_g[c][D] = -theta nu sym([u] (x) n)_{cD}, weighted by the face weight and
+// written back into FL in place: [0..2] w fv_c, [3..5] w F_g[c][D].
+// Enriched cells add the psi parts of both sides and the face terms of their
+// enrichment test rows to rt.
+template <typename T, int NP, int NQ, int NQY, bool ENR, int D, int S>
+__device__ __forceinline__ void aff_flux(const MeshDev& M, const T* s_val, const T* s_grad, T* FL, const T* s_ut,
+                                         const T* s_nut, bool wall, int64_t enr_nb, T tau, int64_t enr, T ht1, T ht2,
+                                         T rt[3], int tofs) {
+  constexpr int T1 = D == 0 ? 1 : 0;
+  constexpr int T2 = D == 2 ? 1 : 2;
+  constexpr int Q1 = aff_q1(D, NQ, NQY), Q2 = aff_q2(D, NQ, NQY), QD = aff_qd(D, NQ, NQY), FP = Q1 * Q2;
+  constexpr int NPTS = NQ * NQY * NQ;
+  constexpr int SD = D == 0 ? 1 : (D == 1 ? NQ : NQ * NQY);  // Gauss-point stride along D
+  constexpr int f = 2 * D + S;
+  constexpr auto& tbd = ct::tab<NP, QD>;
+  constexpr auto& tb1 = ct::tab<NP, Q1>;
+  constexpr auto& tb2 = ct::tab<NP, Q2>;
+  const T nu = T(M.nu), theta = T(M.theta);
+  const T sg = S ? T(1) : T(-1);
+  for (int pt = rotate_tid(tofs); pt < FP; pt += 256) {
+    const int q1 = pt % Q1, q2 = pt / Q1;
+    const int base = D == 0 ? NQ * (q1 + NQY * q2) : (D == 1 ? q1 + NQ * NQY * q2 : q1 + NQ * q2);
+    // own traces: u_c and s_c = d_D u_c + d_c u_D (grad u at [c][d])
+    T um[3], sm[3], up[3], sp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T* pu = s_val + c * NPTS + base;
+      const T* pa = s_grad + (c * 3 + D) * NPTS + base;
+      const T* pb = s_grad + (D * 3 + c) * NPTS + base;
+      T au = 0, as = 0;
+#pragma unroll
+      for (int q = 0; q < QD; ++q) {
+        const T e = T(S ? tbd.E1[q] : tbd.E0[q]);
+        au += e * pu[q * SD];
+        as += e * (c == D ? T(2) * pa[q * SD] : pa[q * SD] + pb[q * SD]);
+      }
+      um[c] = au;
+      sm[c] = as;
+    }
+    T* fo = FL + aff_foff(f, NQ, NQY) + pt;
+    if (!wall) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        up[c] = fo[c * FP];
+        sp[c] = fo[(3 + c) * FP];
+      }
+    }
+    T psim = 0, gpsim[3] = {0, 0, 0};
+    if (ENR) {
+      const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + f] + pt) * 4;
+      psim = T(ps[0]);
+      gpsim[0] = T(ps[1]);
+      gpsim[1] = T(ps[2]);
+      gpsim[2] = T(ps[3]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        um[c] += psim * s_ut[c];
+        sm[c] += s_ut[c] * gpsim[D] + s_ut[D] * gpsim[c];
+      }
+    }
+    if (wall) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        up[c] = -um[c];
+        sp[c] = sm[c];
+      }
+    } else if (enr_nb >= 0) {
+      const double* ps = M.psi + ((size_t)enr_nb * M.psi_pts + M.psi_off[1 + 2 * D + (1 - S)] + pt) * 4;
+      const T psip = T(ps[0]);
+      const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
+      const T* ut = s_nut + f * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        up[c] += psip * ut[c];
+        sp[c] += ut[c] * gpp[D] + ut[D] * gpp[c];
+      }
+    }
+    // n = sg e_D
+    const T unm = sg * um[D], unp = sg * up[D];
+    const T am = unm < 0 ? -unm : unm, ap = unp < 0 ? -unp : unp;
+    const T lam = T(2) * (am > ap ? am : ap);
+    const T wf = T(tb1.w[q1]) * T(tb2.w[q2]) * ht1 * ht2;
+    const T hth = T(0.5) * theta * nu * sg;
+    T Fg[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T jmp = um[c] - up[c];
+      const T fv = T(0.5) * (um[c] * unm + up[c] * unp) + T(0.5) * lam * jmp - T(0.5) * nu * sg * (sm[c] + sp[c]) +
+                   tau * nu * jmp;
+      // F_g[c][D] = -theta nu/2 (jmp_c n_D + jmp_D n_c)
+      Fg[c] = (c == D ? -T(2) : -T(1)) * hth * jmp;
+      fo[c * FP] = wf * fv;
+      fo[(3 + c) * FP] = wf * Fg[c];
+      if (ENR) rt[c] += wf * (psim * fv + Fg[c] * gpsim[D]);
+    }
+    if (ENR) rt[D] += wf * (Fg[T1] * gpsim[T1] + Fg[T2] * gpsim[T2]);
+  }
+}
+
+// Spread the weighted fluxes of face f = 2 D + S onto the Gauss point
+// (qx, qy, qz) of the normal line through it: V_c += e fv_c, G[c][D] += e
+// F_g[c][D] and G[D][c] += e F_g[D][c] (c != D), with e the extrapolation
+// weight of the point's position along D (s_ext).
+template <typename T, int NQ, int NQY, int D, int S>
+__device__ __forceinline__ void aff_spread(const T* FL, const T* s_ext, int qx, int qy, int qz, T V[3], T G[3][3]) {
+  constexpr int Q1 = aff_q1(D, NQ, NQY), FP = Q1 * aff_q2(D, NQ, NQY);
+  const int qd = D == 0 ? qx : (D == 1 ? qy : qz);
+  const int q1 = D == 0 ? qy : qx;
+  const int q2 = D == 2 ? qy : qz;
+  // s_ext: [rule NQ | NQY][E0 | E1][8]
+  const T e = s_ext[((D == 1 ? 1 : 0) * 2 + S) * 8 + qd];
+  const T* F = FL + aff_foff(2 * D + S, NQ, NQY) + q1 + Q1 * q2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    V[c] += e * F[c * FP];
+    const T g = e * F[(3 + c) * FP];
+    G[c][D] += g;
+    if (c != D) G[D][c] += g;
+  }
+}
+
+template <typename T, int NP, int NQ, int NQY, bool ENR>
+__device__ __forceinline__ void vel_cell_affine(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
+                                                int layer_lo, int nlayers) {
+  using Sh = AffShape<T, NP, NQ, NQY>;
+  constexpr int NP3 = Sh::NP3, NPTS = Sh::NPTS;
+  __shared__ T s_r0[3 * NP3];
+  __shared__ T s_vol[Sh::VOL];
+  __shared__ T s_fl[Sh::FL];
+  __shared__ T s_ut[3];
+  __shared__ T s_nut[18];
+  __shared__ T s_red[3 * 4];
+  __shared__ T s_tab[FaceTab<NP, NQ, NQY>::size];
+  __shared__ T s_ext[32];
+  const int tid = threadIdx.x;
+  constexpr int nt = 256;  // workgroup size of every velocity launch
+
+  const int ex = b % M.nx;
+  const int t0 = b / M.nx;
+  int ey, ez;
+  int64_t enr = -1;
+  if (ENR) {
+    const int slot = t0 % M.nslots;
+    ez = t0 / M.nslots;
+    ey = (slot == M.lower_slot) ? 0 : M.ny - 1;
+    enr = b;
+  } else {
+    ey = layer_lo + t0 % nlayers;
+    ez = t0 / nlayers;
+  }
+  const int64_t e = ex + (int64_t)M.nx * (ey + (int64_t)M.ny * ez);
+  const T hx = T(M.hx), hz = T(M.hz), hy = T(M.hy[ey]);
+  const T ix = T(M.ihx), iy = T(M.ihy[ey]), iz = T(M.ihz);
+
+  const double* tab = M.tab;
+  using Sx = ct::MatS<NP, NQ>;
+  using Sy = ct::MatS<NP, NQY>;
+  using Dx = ct::MatD<NP, NQ>;
+  using Dy = ct::MatD<NP, NQY>;
+  constexpr auto& tbx = ct::tab<NP, NQ>;
+  constexpr auto& tby = ct::tab<NP, NQY>;
+  constexpr bool MEM = sizeof(T) == 8;
+  constexpr TabLayout TL = tab_layout(NP, NQ, NQY);
+  const double* mSx = tab + TL.S;
+  const double* mDx = tab + TL.D;
+  const double* mSy = tab + (ENR ? TL.Sy : TL.S);
+  const double* mDy = tab + (ENR ? TL.Dy : TL.D);
+
+  T* s_u = s_r0;
+  T* s_val = s_vol;             // [c][pt]
+  T* s_grad = s_vol + 3 * NPTS; // [c][d][pt]
+  T* tA = s_grad;               // (NQ, NP, NP) x 3
+  T* tB = tA + Sh::TA;          // (NQ, NQY, NP) x 3
+  T* s_nl = Sh::NL_EARLY ? tB + Sh::TB : s_grad;
+  for (int i = tid; i < 3 * NP3; i += nt) s_u[i] = u[e * 3 * NP3 + i];
+  if (ENR && tid < 3) s_ut[tid] = u[M.enr_off + enr * 3 + tid];
+  NbLines<T, NP> nbl;
+  nb_fetch<T, NP>(M, u, ex, ey, ez, nbl);
+  load_face_tab<T, NP, NQ, NQY, ENR>(tab, s_tab);
+  if (tid < 32) {
+    const int rule = tid >> 4, side = (tid >> 3) & 1, q = tid & 7;
+    double v = 0.0;
+    if (rule == 0 && q < NQ) v = side ? tbx.E1[q < NQ ? q : 0] : tbx.E0[q < NQ ? q : 0];
+    if (rule == 1 && q < NQY) v = side ? tby.E1[q < NQY ? q : 0] : tby.E0[q < NQY ? q : 0];
+    s_ext[tid] = T(v);
+  }
+  // faces: neighbours and penalties (uniform over the workgroup)
+  const FaceNb nb[6] = {face_nb(M, ex, ey, ez, 0, 0), face_nb(M, ex, ey, ez, 0, 1), face_nb(M, ex, ey, ez, 1, 0),
+                        face_nb(M, ex, ey, ez, 1, 1), face_nb(M, ex, ey, ez, 2, 0), face_nb(M, ex, ey, ez, 2, 1)};
+  const T ihown[3] = {ix, iy, iz};
+  T tau[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int D = f >> 1;
+    const T ihd = ihown[D];
+    if (nb[f].wall) tau[f] = T(M.pen * M.wall_mult) * ihd;
+    else if (D != 1) tau[f] = T(M.pen) * ihd;
+    else {
+      const T ihn = T(M.ihy[nb[f].nidx1]);
+      tau[f] = T(M.pen) * (ihd > ihn ? ihd : ihn);
+    }
+  }
+  const int y0 = ey == 0 ? M.ny - 1 : ey - 1, y1 = ey + 1 == M.ny ? 0 : ey + 1;
+  __syncthreads();
+
+  // values at the Gauss points: x, y, z interpolation sweeps; the
+  // neighbours' node layers go to LDS with the last one (or right after it)
+  sweep_c<0, NP, NP, NP, NQ, false, false, Sx, 256, MEM>(s_u, NP3, tA, NQ * NP * NP, T(1), 3, 0, mSx);
+  __syncthreads();
+  sweep_c<1, NQ, NP, NP, NQY, false, false, Sy, 256, MEM>(tA, NQ * NP * NP, tB, NQ * NQY * NP, T(1), 3, 0, mSy);
+  __syncthreads();
+  sweep_c<2, NQ, NQY, NP, NQ, false, false, Sx, 256, MEM>(tB, NQ * NQY * NP, s_val, NPTS, T(1), 3, 0, mSx);
+  if (!Sh::NL_EARLY) __syncthreads();
+  nb_store<T, NP, NQ, false>(M, nbl, s_nl, s_nut, ex, ey, ez, ix, iz, T(M.ihy[y0]), T(M.ihy[y1]));
+  __syncthreads();
+
+  // neighbour traces of all six faces (each direction on whole wavefronts)
+  T* FL = s_fl;
+  aff_nb_traces<T, NP, NQ, NQY, 0>(s_nl, s_tab, FL, nb[0].wall, nb[1].wall, iy, iz, 0);
+  aff_nb_traces<T, NP, NQ, NQY, 1>(s_nl, s_tab, FL, nb[2].wall, nb[3].wall, ix, iz, 128);
+  aff_nb_traces<T, NP, NQ, NQY, 2>(s_nl, s_tab, FL, nb[4].wall, nb[5].wall, ix, iy, 64);
+  __syncthreads();
+
+  // gradients by collocation through the Gauss points (over the layers)
+  constexpr int NLG = 3 * NPTS / NQ;
+  constexpr int NLY = 3 * NPTS / NQY;
+  sweep_c<0, NQ, NQY, NQ, NQ, false, false, Dx, 256, MEM>(s_val, NPTS, s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0, mDx);
+  sweep_c<1, NQ, NQY, NQ, NQY, false, false, Dy, 256, MEM>(s_val, NPTS, s_grad + 1 * NPTS, 3 * NPTS, iy, 3,
+                                                           NLG % 256, mDy);
+  sweep_c<2, NQ, NQY, NQ, NQ, false, false, Dx, 256, MEM>(s_val, NPTS, s_grad + 2 * NPTS, 3 * NPTS, iz, 3,
+                                                          (NLG + NLY) % 256, mDx);
+  __syncthreads();
+
+  // numerical fluxes of all six faces (in place; one face per wavefront)
+  T rt[3] = {0, 0, 0};
+  aff_flux<T, NP, NQ, NQY, ENR, 0, 0>(M, s_val, s_grad, FL, s_ut, s_nut, nb[0].wall, nb[0].enr_nb, tau[0], enr, hy,
+                                      hz, rt, 0);
+  aff_flux<T, NP, NQ, NQY, ENR, 0, 1>(M, s_val, s_grad, FL, s_ut, s_nut, nb[1].wall, nb[1].enr_nb, tau[1], enr, hy,
+                                      hz, rt, 64);
+  aff_flux<T, NP, NQ, NQY, ENR, 1, 0>(M, s_val, s_grad, FL, s_ut, s_nut, nb[2].wall, nb[2].enr_nb, tau[2], enr, hx,
+                                      hz, rt, 128);
+  aff_flux<T, NP, NQ, NQY, ENR, 1, 1>(M, s_val, s_grad, FL, s_ut, s_nut, nb[3].wall, nb[3].enr_nb, tau[3], enr, hx,
+                                      hz, rt, 192);
+  aff_flux<T, NP, NQ, NQY, ENR, 2, 0>(M, s_val, s_grad, FL, s_ut, s_nut, nb[4].wall, nb[4].enr_nb, tau[4], enr, hx,
+                                      hy, rt, 128);
+  aff_flux<T, NP, NQ, NQY, ENR, 2, 1>(M, s_val, s_grad, FL, s_ut, s_nut, nb[5].wall, nb[5].enr_nb, tau[5], enr, hx,
+                                      hy, rt, 192);
+  __syncthreads();
+
+  // pointwise flux G = w (2 nu eps(u) - u (x) u), plus the face fluxes spread
+  // along the normal lines (gradient tests into G, value tests into V)
+  const T nu = T(M.nu);
+  const T vol = hx * hy * hz;
+  for (int pt = tid; pt < NPTS; pt += nt) {
+    const int qx = pt % NQ, qy = (pt / NQ) % NQY, qz = pt / (NQ * NQY);
+    const T wq = T(tbx.w[qx]) * T(tby.w[qy]) * T(tbx.w[qz]) * vol;
+    T uu[3], gg[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uu[c] = s_val[c * NPTS + pt];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gg[c][d] = s_grad[(c * 3 + d) * NPTS + pt];
+    }
+    T gps[3] = {0, 0, 0};
+    if (ENR) {
+      const double* ps = M.psi + ((size_t)enr * M.psi_pts + pt) * 4;
+      const T psv = T(ps[0]);
+      gps[0] = T(ps[1]);
+      gps[1] = T(ps[2]);
+      gps[2] = T(ps[3]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uu[c] += psv * s_ut[c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gg[c][d] += s_ut[c] * gps[d];
+      }
+    }
+    T G[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        G[c][d] = wq * (nu * (gg[c][d] + gg[d][c]) - uu[c] * uu[d]);
+        if (ENR) rt[c] += G[c][d] * gps[d];
+      }
+    T V[3] = {0, 0, 0};
+    aff_spread<T, NQ, NQY, 0, 0>(FL, s_ext, qx, qy, qz, V, G);
+    aff_spread<T, NQ, NQY, 0, 1>(FL, s_ext, qx, qy, qz, V, G);
+    aff_spread<T, NQ, NQY, 1, 0>(FL, s_ext, qx, qy, qz, V, G);
+    aff_spread<T, NQ, NQY, 1, 1>(FL, s_ext, qx, qy, qz, V, G);
+    aff_spread<T, NQ, NQY, 2, 0>(FL, s_ext, qx, qy, qz, V, G);
+    aff_spread<T, NQ, NQY, 2, 1>(FL, s_ext, qx, qy, qz, V, G);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s_val[c * NPTS + pt] = V[c];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s_grad[(c * 3 + d) * NPTS + pt] = G[c][d];
+    }
+  }
+  __syncthreads();
+
+  // integrate: W = sum_d D_d^T G_d / h_d + V, then transposed interpolation
+  sweep_c_inplace<0, NQ, NQY, NQ, true, Dx, 256, MEM>(s_grad + 0 * NPTS, 3 * NPTS, ix, 3, 0, mDx);
+  sweep_c_inplace<1, NQ, NQY, NQ, true, Dy, 256, MEM>(s_grad + 1 * NPTS, 3 * NPTS, iy, 3, NLG % 256, mDy);
+  __syncthreads();
+  {
+    T* tB2 = s_fl;                        // (NQ, NQY, NP) x 3
+    T* tA2 = s_grad;                      // (NQ, NP, NP) x 3
+    for (int t = tid; t < 3 * NQ * NQY; t += nt) {
+      const int c = t / (NQ * NQY), pq = t - c * (NQ * NQY);  // pq = qx + NQ qy
+      const T* gz = s_grad + (c * 3 + 2) * NPTS + pq;
+      const T* wx = s_grad + (c * 3 + 0) * NPTS + pq;
+      const T* wy = s_grad + (c * 3 + 1) * NPTS + pq;
+      const T* vv = s_val + c * NPTS + pq;
+      T g[NQ], w[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) g[q] = gz[q * NQ * NQY];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) w[q] = wx[q * NQ * NQY] + wy[q * NQ * NQY] + vv[q * NQ * NQY];
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) {
+        T sacc = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sacc += T(MEM ? mDx[q * NQ + m] : tbx.D[q][m]) * g[q];
+        w[m] += iz * sacc;
+      }
+      T* o = tB2 + c * (NQ * NQY * NP) + pq;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        T sacc = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sacc += T(MEM ? mSx[q * NP + i] : tbx.S[q][i]) * w[q];
+        o[i * NQ * NQY] = sacc;
+      }
+    }
+    __syncthreads();
+    sweep_c<1, NQ, NQY, NP, NP, true, false, Sy, 256, MEM>(tB2, NQ * NQY * NP, tA2, NQ * NP * NP, T(1), 3, 0, mSy);
+    __syncthreads();
+    T* s_r = s_r0;
+    sweep_c<0, NQ, NP, NP, NP, true, false, Sx, 256, MEM>(tA2, NQ * NP * NP, s_r, NP3, T(1), 3, 0, mSx);
+    __syncthreads();
+    for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
+  }
+  if (ENR) {
+    block_sum3(rt, s_red);
+    if (tid < 3) r[M.enr_off + enr * 3 + tid] = rt[0];
+  }
+}
+
 // One cell: block-local index b within its launch (regular cells: layer range
 // [layer_lo, layer_lo + nlayers); enriched cells: the enriched index).
 template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
-__device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
-                                         int layer_lo, int nlayers) {
+__device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
+                                                 int layer_lo, int nlayers) {
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr int NP3 = Sh::NP3, NPTS = Sh::NPTS;
   __shared__ T s_u[3 * NP3];
@@ -1019,8 +1513,39 @@ __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__
   }
 }
 
+// FP32 affine cells take the folded-face path (vel_cell below).
+template <typename T>
+__host__ __device__ constexpr bool vel_use_affine() { return sizeof(T) == 4; }
+
+// Workgroups per CU the launch bounds plan for: the folded-face path is
+// limited by its LDS, the general path by registers.
+// (FP64 enriched cells keep up to 256 registers, other FP64 cells 168, FP32
+// cells 128: below that they spill.)
 template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
-__global__ __launch_bounds__(256, CURVED ? 2 : 3) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
+__host__ __device__ constexpr int vel_wg_per_cu() {
+  if (CURVED) return 2;
+  if (!vel_use_affine<T>() || !AffShape<T, NP, NQ, NQY>::fits) return 3;
+  const int by_lds = (160 * 1024) / AffShape<T, NP, NQ, NQY>::BYTES;
+  const int by_regs = sizeof(T) == 8 ? (ENR ? 2 : 3) : 4;
+  return by_lds < by_regs ? by_lds : by_regs;
+}
+
+// FP32 affine cells take the folded-face path (814 us against 1009 us for
+// the general one on the 64x32x32 k = 4 mesh).  In FP64 that path reads one
+// 8-byte LDS value per FMA in its extrapolations and lost to the general
+// path's line-owned face phases (1516 us against 1430 us), so FP64, curved
+// cells and the largest degrees take the general path.
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
+__device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
+                                         int layer_lo, int nlayers) {
+  if constexpr (!CURVED && vel_use_affine<T>() && AffShape<T, NP, NQ, NQY>::fits)
+    vel_cell_affine<T, NP, NQ, NQY, ENR>(M, u, r, b, layer_lo, nlayers);
+  else
+    vel_cell_general<T, NP, NQ, NQY, ENR, CURVED>(M, u, r, b, layer_lo, nlayers);
+}
+
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
+__global__ __launch_bounds__(256, (vel_wg_per_cu<T, NP, NQ, NQY, ENR, CURVED>())) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
                                                   int layer_lo, int nlayers) {
   // contiguous cell ranges per XCD (workgroups are dealt round-robin over
   // the 8 XCDs), so neighbouring cells share an L2
@@ -1047,7 +1572,7 @@ namespace {
 // item i.  Each cell runs exactly the code of the single-mesh kernel, so the
 // results are bit-for-bit the same.
 template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
-__global__ __launch_bounds__(256, CURVED ? 2 : 3) void vel_kernel_batched(const VelBatchItem* __restrict__ items,
+__global__ __launch_bounds__(256, (vel_wg_per_cu<T, NP, NQ, NQY, ENR, CURVED>())) void vel_kernel_batched(const VelBatchItem* __restrict__ items,
                                                           const int64_t* __restrict__ prefix, int nitems) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = nitems;
