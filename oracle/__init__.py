@@ -78,6 +78,10 @@ def lib():
         L.orc_enrichment_active.argtypes = [P, _D, _D, ctypes.POINTER(ctypes.c_int32)]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
         L.orc_face_points.argtypes = [P, ctypes.c_int64, ctypes.c_int, _D]
+        L.orc_viscous_multiscale.argtypes = [P, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_int, _I64,
+                                             ctypes.c_int64, _D]
+        L.orc_eddy_viscosity_point.argtypes = [P, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_int64, _D,
+                                               _D]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         _LIB = L
@@ -435,3 +439,45 @@ def face_points(cfg, e, f):
         raise ValueError(f"orc_face_points failed: {n}")
     o = out[: 7 * n].reshape(n, 7)
     return o[:, :3].copy(), o[:, 3:6].copy(), o[:, 6].copy()
+
+
+C_DES, BETA = 0.85, 6.0   # Sec. 2.2, eq. ydes: calibrated C_DES and the smoothing exponent
+
+
+def viscous_multiscale(cfg, u, u_nut=None, tau=None, tau_nodes=None, c_des=C_DES, beta=BETA, clip=True, cells=None):
+    """A u = -F^nu_e of Sec. 4.2, eq. viscous_multiscale, for every velocity test
+    function (velocity layout); nu_t from the enrichment coefficients of u_nut
+    (default: u).  clip=False drops the limit of eq. minvt (pins only)."""
+    p = params(cfg)
+    u = _f64(u)
+    n = num_dofs(cfg, 0)
+    if u.size != n:
+        raise ValueError("u has the wrong size")
+    un = u if u_nut is None else _f64(u_nut)
+    if un.size != n:
+        raise ValueError("u_nut has the wrong size")
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    cells = _cells(cfg, cells)
+    r = np.zeros(n)
+    rc = lib().orc_viscous_multiscale(ctypes.byref(p), _ptr(u), _ptr(un), _ptr(t) if t is not None else None,
+                                      _ptr(tn) if tn is not None else None, float(c_des), float(beta), int(clip),
+                                      cells.ctypes.data_as(_I64), cells.size, _ptr(r))
+    if rc:
+        raise RuntimeError(f"orc_viscous_multiscale failed: {rc}")
+    return r
+
+
+def eddy_viscosity_point(cfg, u_nut, e, xi, tau=None, tau_nodes=None, c_des=C_DES, beta=BETA):
+    """(nu_t, y, y+, |eps(u~)|) at reference point xi of enriched cell e (Sec. 2.2, eqs. mix, lmix, ydes)."""
+    p = params(cfg)
+    un = _f64(u_nut)
+    t = _f64(tau) if tau is not None else None
+    tn = _tau_nodes(cfg, tau_nodes) if tau_nodes is not None else None
+    out = np.zeros(4)
+    rc = lib().orc_eddy_viscosity_point(ctypes.byref(p), _ptr(un), _ptr(t) if t is not None else None,
+                                        _ptr(tn) if tn is not None else None, float(c_des), float(beta), int(e),
+                                        _ptr(_f64(xi)), _ptr(out))
+    if rc:
+        raise RuntimeError(f"orc_eddy_viscosity_point failed: {rc}")
+    return out

@@ -1434,6 +1434,295 @@ int orc_cell_map(const orc_params *P, int64_t e, const double *xi, double *X, do
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Multiscale viscous operator (Sec. 2.2 and Sec. 4.2)                        */
+/* ------------------------------------------------------------------------ */
+
+/* Eddy viscosity of the RANS scale at reference point xi of enriched cell e
+ * (eq. mix): nu_t = l_mix^2 |eps(u~)|, |eps| = sqrt(2 eps : eps), with the
+ * mixing length l_mix = kappa y_DES (1 - exp(-y+/A+)) (eq. lmix), the smooth
+ * DES limit y_DES = (y^-beta + (C_DES h)^-beta)^(-1/beta) (eq. ydes; written
+ * as y C h / (y^beta + (C h)^beta)^(1/beta), which is 0 at the wall), and
+ * h = dy_e / (k+1) the wall-normal cell width over k+1.  u~ = psi ut (l = 0:
+ * ut the cell's three enrichment coefficients), so grad u~ = ut (x) grad psi.
+ * y = y_h (the wall distance of Sec. 3.2), y+ = y_h sqrt(tau_w)/nu.
+ * out: nu_t, y, y+, |eps(u~)|.  Flat walls only. */
+static void eddy_point(const ctx *C, int64_t e, const double xi[3], const double Ji[3][3], const double ut[3],
+                       const psi_pt *ps, double c_des, double beta, double out[4]) {
+  int ex, ey, ez;
+  cell_index(C, e, &ex, &ey, &ez);
+  double yh, gyh[3], tw, gtw[3];
+  wall_fields(C, e, xi, Ji, &yh, gyh, &tw, gtw);
+  double yp = yh * sqrt(tw) / C->P.nu;
+  double h = (C->eta[ey + 1] - C->eta[ey]) / (C->P.k_u + 1);
+  double ch = c_des * h;
+  double ydes = yh * ch / pow(pow(yh, beta) + pow(ch, beta), 1.0 / beta);
+  double lmix = C->P.kappa * ydes * (1.0 - exp(-yp / C->P.A_plus));
+  double eps2 = 0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double eij = 0.5 * (ut[i] * ps->g[j] + ut[j] * ps->g[i]);
+      eps2 += eij * eij;
+    }
+  double em = sqrt(2.0 * eps2);
+  out[0] = lmix * lmix * em;
+  out[1] = yh;
+  out[2] = yp;
+  out[3] = em;
+}
+
+typedef struct {
+  double ub[3], gb[3][3];  /* polynomial part u_bar and its gradient [c][d]     */
+  double ut[3], gt[3][3];  /* enrichment part u~ = psi ut and its gradient        */
+  double psi, gpsi[3];     /* psi and grad psi (zero outside enriched cells)      */
+  double nut;              /* eddy viscosity (zero outside enriched cells)        */
+  int enriched;
+} ms_pt;
+
+/* Both scales of the velocity at xi of cell e, and nu_t from the enrichment
+ * coefficients of unut. */
+static void eval_ms(const ctx *C, const double *u, const double *unut, int64_t e, const double xi[3],
+                    const double Ji[3][3], double c_des, double beta, ms_pt *o, double *bv, double (*bg)[3]) {
+  int n = C->npu, np3 = n * n * n;
+  basis3(n, C->glu, xi, Ji, bv, bg);
+  for (int c = 0; c < 3; ++c) {
+    const double *uc = u + ((int64_t)e * 3 + c) * np3;
+    double s = 0, g0 = 0, g1 = 0, g2 = 0;
+    for (int B = 0; B < np3; ++B) {
+      s += bv[B] * uc[B];
+      g0 += bg[B][0] * uc[B];
+      g1 += bg[B][1] * uc[B];
+      g2 += bg[B][2] * uc[B];
+    }
+    o->ub[c] = s;
+    o->gb[c][0] = g0; o->gb[c][1] = g1; o->gb[c][2] = g2;
+    o->ut[c] = 0;
+    for (int d = 0; d < 3; ++d) o->gt[c][d] = 0;
+  }
+  o->psi = 0;
+  o->gpsi[0] = o->gpsi[1] = o->gpsi[2] = 0;
+  o->nut = 0;
+  o->enriched = (C->enr[e] >= 0);
+  if (!o->enriched) return;
+  psi_pt ps;
+  eval_psi(C, e, xi, Ji, &ps);
+  o->psi = ps.psi;
+  for (int d = 0; d < 3; ++d) o->gpsi[d] = ps.g[d];
+  const double *ut = u + C->ncell * 3 * np3 + C->enr[e] * 3;
+  const double *un = unut + C->ncell * 3 * np3 + C->enr[e] * 3;
+  for (int c = 0; c < 3; ++c) {
+    o->ut[c] = ps.psi * ut[c];
+    for (int d = 0; d < 3; ++d) o->gt[c][d] = ut[c] * ps.g[d];
+  }
+  double ev[4];
+  eddy_point(C, e, xi, Ji, un, &ps, c_des, beta, ev);
+  o->nut = ev[0];
+}
+
+/* A(v, u) = -F^nu_e(v_bar, v~, u_bar, u~) of eq. viscous_multiscale for every
+ * test function v of cell e (v_bar = N_B e_c; v~ = psi e_c in an enriched
+ * cell), with F^a(w) = 2 a eps(w) and, as the paper's rows and columns read:
+ *   volume:  (eps(v_bar), F^nu(u_bar))_e + (eps(v_bar), F^nuhat(u~))_e
+ *            + (eps(v~), F^{nu+nu_t}(u~))_e,
+ *            nuhat = min(nu + nu_t, 2 sqrt(nu (nu + nu_t))) (eq. minvt; clip = 0
+ *            keeps nu + nu_t, for the coercivity pins only);
+ *   faces, by class (own cell "-", outward n, [w] = w- - w+):
+ *   regular (no enriched side): (1/2 F^nu(v_bar), [u_bar] (x) n)
+ *            - (v_bar, {{F^nu(u_bar)}} n) + (v_bar, tau nu [u_bar]);
+ *   interface (exactly one side enriched, u~ = 0 on the other):
+ *            (1/2 F^nu(v_bar), [u] (x) n) - (v, {{F^nu(u_bar)}} n) + (v, tau nu [u])
+ *            for v = v_bar, and the last two terms for v = v~;
+ *   inner enriched (both sides enriched; a wall of an enriched cell, whose
+ *   mirror side is enriched too):
+ *            (1/2 F^nu(v_bar), [u_bar] (x) n) - (v_bar, {{F^nu(u_bar)}} n)
+ *            - (v, {{F^{nu+nu_t}(u~)}}_w n) + (v, tau nu [u]) for v = v_bar, v~,
+ *            and (w- F^{nu+nu_t}(v~), [u] (x) n) for v = v~,
+ * with u = u_bar + u~, {{.}} the mean with weights 1/2 and {{.}}_w the
+ * harmonic weights w- = (nu + nu_t+)/(2 nu + nu_t- + nu_t+), w+ = (nu +
+ * nu_t-)/(2 nu + nu_t- + nu_t+) (eq. harmweights).  Walls: mirror data
+ * u+ = -u-, grad u+ = grad u-, nu_t+ = nu_t-, tau x wall_ip_mult.  The
+ * penalty carries nu alone and tau as in the velocity residual.  nu_t comes
+ * from the enrichment coefficients of unut.  M du/dt = -A u is the viscous
+ * substep of the paper's scheme. */
+static void visc_ms_cell(const ctx *C, const double *u, const double *unut, int64_t e, double *r, double c_des,
+                         double beta, int clip, double *bv, double (*bg)[3], double *bv2, double (*bg2)[3]) {
+  int n = C->npu, np3 = n * n * n;
+  double nu = C->P.nu;
+  double *re = r + (int64_t)e * 3 * np3;
+  double rt[3] = {0, 0, 0};
+  for (int i = 0; i < 3 * np3; ++i) re[i] = 0.0;
+  int e_enr = C->enr[e] >= 0;
+
+  /* volume */
+  {
+    const double *q[3], *w[3];
+    int nq[3];
+    for (int a = 0; a < 3; ++a) { q[a] = vel_q(C, e, a, &w[a]); nq[a] = vel_nq(C, e, a); }
+    for (int c3 = 0; c3 < nq[2]; ++c3)
+      for (int b = 0; b < nq[1]; ++b)
+        for (int a = 0; a < nq[0]; ++a) {
+          double xi[3] = {q[0][a], q[1][b], q[2][c3]}, X[3], J[3][3], Ji[3][3];
+          cell_map(C, e, xi, X, J);
+          double wq = fabs(inv3(J, Ji)) * w[0][a] * w[1][b] * w[2][c3];
+          ms_pt p;
+          eval_ms(C, u, unut, e, xi, Ji, c_des, beta, &p, bv, bg);
+          double nt = nu + p.nut;
+          double nhat = clip ? fmin(nt, 2.0 * sqrt(nu * nt)) : nt;
+          for (int c = 0; c < 3; ++c) {
+            double G[3];
+            for (int d = 0; d < 3; ++d)
+              G[d] = nu * (p.gb[c][d] + p.gb[d][c]) + nhat * (p.gt[c][d] + p.gt[d][c]);
+            double *rc = re + c * np3;
+            for (int B = 0; B < np3; ++B) rc[B] += wq * (bg[B][0] * G[0] + bg[B][1] * G[1] + bg[B][2] * G[2]);
+            if (p.enriched) {
+              /* eps(psi e_c) : F = sum_d d_d psi F[c][d] for symmetric F */
+              double s = 0;
+              for (int d = 0; d < 3; ++d) s += p.gpsi[d] * nt * (p.gt[c][d] + p.gt[d][c]);
+              rt[c] += wq * s;
+            }
+          }
+        }
+  }
+
+  /* faces */
+  double vol_e = cell_volume(C, e, 0);
+  for (int f = 0; f < 6; ++f) {
+    int d = f / 2, s = f % 2;
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    int64_t nb = face_neighbor(C, e, d, s);
+    int wall = (nb < 0);
+    int nb_enr = !wall && C->enr[nb] >= 0;
+    int inner = e_enr && (wall || nb_enr);  /* otherwise an enriched cell's face is an interface */
+    const double *q1, *w1, *q2, *w2;
+    int n1, n2;
+    face_rule(C, e, nb, t1, t2, &q1, &w1, &n1, &q2, &w2, &n2);
+    double area = 0;
+    for (int b = 0; b < n2; ++b)
+      for (int a = 0; a < n1; ++a) {
+        double xi[3], X[3], Ji[3][3], nv[3], dA;
+        xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        area += dA * w1[a] * w2[b];
+      }
+    double pf = C->P.ip_factor_u * (double)(n) * (double)(n);
+    double tauF = wall ? C->P.wall_ip_mult * pf * area / vol_e
+                       : pf * fmax(area / vol_e, area / cell_volume(C, nb, 0));
+    for (int b = 0; b < n2; ++b)
+      for (int a = 0; a < n1; ++a) {
+        double xi[3], xn[3], X[3], Ji[3][3], Xn[3], Jn[3][3], Jin[3][3], nv[3], dA;
+        xi[d] = s; xi[t1] = q1[a]; xi[t2] = q2[b];
+        face_point(C, e, d, s, xi, X, Ji, nv, &dA);
+        double wf = dA * w1[a] * w2[b];
+        ms_pt pm, pp;
+        eval_ms(C, u, unut, e, xi, Ji, c_des, beta, &pm, bv, bg);
+        if (wall) {
+          pp = pm;
+          for (int c = 0; c < 3; ++c) { pp.ub[c] = -pm.ub[c]; pp.ut[c] = -pm.ut[c]; }
+        } else {
+          xn[d] = 1 - s; xn[t1] = xi[t1]; xn[t2] = xi[t2];
+          cell_map(C, nb, xn, Xn, Jn);
+          inv3(Jn, Jin);
+          eval_ms(C, u, unut, nb, xn, Jin, c_des, beta, &pp, bv2, bg2);
+        }
+        double jb[3], ju[3], Eb[3], Et[3];
+        double wm = 0.5, wp = 0.5;
+        if (inner) {
+          double den = 2.0 * nu + pm.nut + pp.nut;
+          wm = (nu + pp.nut) / den;
+          wp = (nu + pm.nut) / den;
+        }
+        for (int c = 0; c < 3; ++c) {
+          jb[c] = pm.ub[c] - pp.ub[c];
+          ju[c] = (pm.ub[c] + pm.ut[c]) - (pp.ub[c] + pp.ut[c]);
+          double sb = 0, st = 0;
+          for (int k = 0; k < 3; ++k) {
+            sb += 0.5 * nu * ((pm.gb[c][k] + pm.gb[k][c]) + (pp.gb[c][k] + pp.gb[k][c])) * nv[k];
+            st += (wm * (nu + pm.nut) * (pm.gt[c][k] + pm.gt[k][c]) +
+                   wp * (nu + pp.nut) * (pp.gt[c][k] + pp.gt[k][c])) * nv[k];
+          }
+          Eb[c] = sb;
+          Et[c] = inner ? st : 0.0;
+        }
+        /* test functions N_B e_c */
+        const double *J = inner ? jb : ju;
+        for (int c = 0; c < 3; ++c) {
+          double fv = -Eb[c] - Et[c] + tauF * nu * ju[c];
+          double Fg[3];
+          for (int k = 0; k < 3; ++k) Fg[k] = nu * 0.5 * (J[c] * nv[k] + J[k] * nv[c]);
+          double *rc = re + c * np3;
+          for (int B = 0; B < np3; ++B)
+            rc[B] += wf * (bv[B] * fv + bg[B][0] * Fg[0] + bg[B][1] * Fg[1] + bg[B][2] * Fg[2]);
+        }
+        /* test functions psi e_c */
+        if (e_enr) {
+          double gn = pm.gpsi[0] * nv[0] + pm.gpsi[1] * nv[1] + pm.gpsi[2] * nv[2];
+          double jg = ju[0] * pm.gpsi[0] + ju[1] * pm.gpsi[1] + ju[2] * pm.gpsi[2];
+          for (int c = 0; c < 3; ++c) {
+            double val;
+            if (inner)
+              val = pm.psi * (-Et[c] + tauF * nu * ju[c]) + wm * (nu + pm.nut) * (ju[c] * gn + jg * nv[c]);
+            else /* interface */
+              val = pm.psi * (-Eb[c] + tauF * nu * ju[c]);
+            rt[c] += wf * val;
+          }
+        }
+      }
+  }
+  if (e_enr) {
+    double *ro = r + C->ncell * 3 * np3 + C->enr[e] * 3;
+    for (int c = 0; c < 3; ++c) ro[c] = rt[c];
+  }
+}
+
+int orc_viscous_multiscale(const orc_params *P, const double *u, const double *u_nut, const double *tau_w,
+                           const double *tau_nodes, double c_des, double beta, int clip, const int64_t *cells,
+                           int64_t ncells, double *r) {
+  ctx C;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
+  if (P->wall_amp != 0.0) { ctx_free(&C); return -4; }
+  ctx_activity(&C, -1);
+  int n = C.npu, np3 = n * n * n;
+  int err = 0;
+#pragma omp parallel
+  {
+    double *bv = (double *)malloc(sizeof(double) * np3 * 2);
+    double(*bg)[3] = (double(*)[3])malloc(sizeof(double) * 3 * np3 * 2);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < ncells; ++i) {
+      int64_t e = cells[i];
+      if (e < 0 || e >= C.ncell) { err = -3; continue; }
+      visc_ms_cell(&C, u, u_nut, e, r, c_des, beta, clip, bv, bg, bv + np3, bg + np3);
+    }
+    free(bv);
+    free(bg);
+  }
+  ctx_free(&C);
+  return err;
+}
+
+/* nu_t, y, y+ and |eps(u~)| at reference point xi of enriched cell e, with the
+ * enrichment coefficients of u_nut (see eddy_point).  Returns -2 for a cell
+ * without enrichment. */
+int orc_eddy_viscosity_point(const orc_params *P, const double *u_nut, const double *tau_w, const double *tau_nodes,
+                             double c_des, double beta, int64_t e, const double *xi, double *out4) {
+  ctx C;
+  if (ctx_init(&C, P, tau_w)) return -1;
+  C.tau_nodes = tau_nodes;
+  if (e < 0 || e >= C.ncell || C.enr[e] < 0 || P->wall_amp != 0.0) { ctx_free(&C); return -2; }
+  ctx_activity(&C, -1);
+  double X[3], J[3][3], Ji[3][3];
+  cell_map(&C, e, xi, X, J);
+  inv3(J, Ji);
+  psi_pt ps;
+  eval_psi(&C, e, xi, Ji, &ps);
+  int np3 = C.npu * C.npu * C.npu;
+  eddy_point(&C, e, xi, Ji, u_nut + C.ncell * 3 * np3 + C.enr[e] * 3, &ps, c_des, beta, out4);
+  ctx_free(&C);
+  return 0;
+}
+
 /* Quadrature points of face f = 2 d + s of cell e with the face rule of the
  * velocity residual (the larger tangential counts of the two adjacent cells).
  * Per point, 7 doubles: X[3], n w dA [3] (outward unit normal times weight
