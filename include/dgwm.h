@@ -314,6 +314,55 @@ int dg_apply_divdiv(const dg_mesh* mesh, const double* tau_d, const double* u, d
 int dg_projection_step(const dg_mesh* mesh, const double* tau_d, const double* u_hat, const double* g, double scale,
                        double* x, void* stream);
 
+/* Points of the eddy-viscosity table: dg_num_enriched(mesh) times the points
+ * of one enriched cell (its volume rule nq_u x nq_wn x nq_u, x fastest, then
+ * the face rules of its faces x=0, x=1, y=0, y=1, z=0, z=1), or a negative
+ * DG_ERR_* code. */
+int64_t dg_eddy_viscosity_points(const dg_mesh* mesh);
+
+/* Eddy viscosity of the RANS scale (paper Sec. 2.2) at every quadrature point
+ * of the enriched cells, from the enrichment coefficients of u (u~ = psi ut,
+ * l = 0, so grad u~ = ut (x) grad psi):
+ *   nu_t = l_mix^2 |eps(u~)|,  |eps| = sqrt(2 eps : eps)             (eq. mix)
+ *   l_mix = kappa y_DES (1 - exp(-y+/A+))                            (eq. lmix)
+ *   y_DES = (y^-beta + (c_des h)^-beta)^(-1/beta), 0 at the wall     (eq. ydes)
+ * with y the wall distance, y+ = y sqrt(tau_w)/nu, h the wall-normal cell
+ * width over k_u + 1, kappa and A+ the mesh's constants and the psi table in
+ * force.  The paper's values are c_des = 0.85 and beta = 6.  Switched-off
+ * cells get 0.  Flat walls only.
+ *   u:   device, dg_num_dofs(mesh, 0) doubles (only its enrichment block is read);
+ *   nut: device output, dg_eddy_viscosity_points(mesh) doubles, layout
+ *        [enriched cell][point] as described there.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved wall), DG_ERR_HIP. */
+int dg_eddy_viscosity(const dg_mesh* mesh, const double* u, double c_des, double beta, double* nut, void* stream);
+
+/* Viscous term of the multiscale method (paper Sec. 4.2, eq.
+ * viscous_multiscale): out(v) = -F^nu_e(v_bar, v~, u_bar, u~) for every test
+ * function v (v_bar = N_B e_c; v~ = psi e_c in enriched cells), with
+ * F^a(w) = 2 a eps(w), the four row blocks and face-class masks of the
+ * equation (adjoint sign -1):
+ *   volume:    (eps(v_bar), F^nu(u_bar) + F^nuhat(u~)) + (eps(v~), F^{nu+nu_t}(u~)),
+ *              nuhat = min(nu + nu_t, 2 sqrt(nu (nu + nu_t)))  (Sec. 4.3, eq. minvt);
+ *   faces without an enriched side (the SIP form of the velocity residual
+ *              with theta = -1): (F^nu(v_bar)/2, [u_bar] (x) n)
+ *              - (v_bar, {{F^nu(u_bar)}} n) + (v_bar, tau nu [u_bar]);
+ *   interface faces (one enriched side): (F^nu(v_bar)/2, [u] (x) n)
+ *              - (v, {{F^nu(u_bar)}} n) + (v, tau nu [u]), the adjoint part for
+ *              v_bar only;
+ *   faces of an enriched cell whose other side is enriched or a wall:
+ *              (F^nu(v_bar)/2, [u_bar] (x) n) - (v_bar, {{F^nu(u_bar)}} n)
+ *              - (v, {{F^{nu+nu_t}(u~)}}_w n) + (v, tau nu [u]), plus
+ *              (w- F^{nu+nu_t}(v~), [u] (x) n) for v~,
+ * u = u_bar + u~, {{.}}_w the harmonic weights of eq. harmweights, mirror data
+ * on walls (u+ = -u-, grad u+ = grad u-, nu_t+ = nu_t-), tau as in
+ * dg_apply_velocity_residual (x wall_ip_mult on walls), velocity quadrature
+ * (R9/R10 rules of the residual).  Linear in u for the given nu_t; the
+ * Helmholtz step of the paper's scheme is (gamma_0/dt) M u + A u = rhs.
+ *   nut: device, from dg_eddy_viscosity (may be NULL without enriched cells);
+ *   u, out: device, dg_num_dofs(mesh, 0) doubles, distinct.  FP64, flat walls.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
+int dg_apply_viscous_multiscale(const dg_mesh* mesh, const double* nut, const double* u, double* out, void* stream);
+
 /* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
  * term, flux eq. ipflux) with homogeneous Neumann data on the walls:
  *   (A p)(q) = sum_e (grad q, grad p)_e + sum_{interior F} [ -1/2 (grad q.n)(p- - p+)

@@ -216,6 +216,29 @@ class Mesh:
                                                  _dptr(x), _stream_ptr(stream)))
         return x
 
+    def eddy_viscosity(self, u, c_des=0.85, beta=6.0, nut=None, stream=None):
+        """nu_t of the RANS scale at every enriched quadrature point (Sec. 2.2),
+        from the enrichment coefficients of u (float64 device tensor)."""
+        import torch
+        self._check_f64(u, self.n_vel, "u")
+        n = _lib.check(_lib.lib().dg_eddy_viscosity_points(self.handle))
+        if nut is None:
+            nut = torch.empty(max(int(n), 1), dtype=torch.float64, device=self.device)
+        _lib.check(_lib.lib().dg_eddy_viscosity(self.handle, _dptr(u), float(c_des), float(beta), _dptr(nut),
+                                                _stream_ptr(stream)))
+        return nut[:n]
+
+    def apply_viscous_multiscale(self, nut, u, out=None, stream=None):
+        """out = A u, the multiscale viscous operator of Sec. 4.2 (FP64)."""
+        import torch
+        self._check_f64(u, self.n_vel, "u")
+        if out is None:
+            out = torch.empty_like(u)
+        self._check_f64(out, self.n_vel, "out")
+        _lib.check(_lib.lib().dg_apply_viscous_multiscale(self.handle, _dptr(nut) if nut is not None else None,
+                                                          _dptr(u), _dptr(out), _stream_ptr(stream)))
+        return out
+
     def enrichment_active(self, stream=None):
         """Activity flags (int32 device tensor, 1 on / 0 switched off) of the
         enriched cells in the current space."""

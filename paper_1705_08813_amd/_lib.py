@@ -67,6 +67,9 @@ _SIGS = {
     "dg_apply_divdiv": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "dg_projection_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
     "dg_enrichment_active": (ctypes.c_int, [_VP, _VP, _VP]),
+    "dg_eddy_viscosity_points": (ctypes.c_int64, [_VP]),
+    "dg_eddy_viscosity": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
+    "dg_apply_viscous_multiscale": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "dg_num_dofs": (ctypes.c_int64, [_VP, ctypes.c_int]),
     "dg_num_enriched": (ctypes.c_int64, [_VP]),
     "dg_destroy_mesh": (None, [_VP]),

@@ -469,6 +469,30 @@ int dg_projection_step(const dg_mesh* m, const double* tau_d, const double* u_ha
   return launch_projection_step(m, tau_d, u_hat, g, scale, x, static_cast<hipStream_t>(stream));
 }
 
+int64_t dg_eddy_viscosity_points(const dg_mesh* m) {
+  if (!m) return set_error(DG_ERR_ARG, "mesh is NULL");
+  return m->nenr * (int64_t)m->psi_pts;
+}
+
+int dg_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double beta, double* nut, void* stream) {
+  if (!m || !u || !nut) return set_error(DG_ERR_ARG, "mesh/u/nut is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "eddy viscosity: flat meshes only");
+  if (!(c_des > 0) || !std::isfinite(c_des) || !(beta > 0) || !std::isfinite(beta))
+    return set_error(DG_ERR_ARG, "c_des and beta must be positive and finite");
+  if (static_cast<const void*>(u) == static_cast<const void*>(nut)) return set_error(DG_ERR_ARG, "u and nut must not alias");
+  if (!aligned256(u) || !aligned256(nut)) return set_error(DG_ERR_ARG, "u and nut must be 256-byte aligned");
+  return launch_eddy_viscosity(m, u, c_des, beta, nut, static_cast<hipStream_t>(stream));
+}
+
+int dg_apply_viscous_multiscale(const dg_mesh* m, const double* nut, const double* u, double* out, void* stream) {
+  if (!m || !u || !out || (!nut && m->nenr > 0)) return set_error(DG_ERR_ARG, "mesh/nut/u/out is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "multiscale viscous operator: flat meshes only");
+  if (u == out || (nut && (nut == u || nut == out))) return set_error(DG_ERR_ARG, "u, out and nut must not alias");
+  if (!aligned256(u) || !aligned256(out) || (nut && !aligned256(nut)))
+    return set_error(DG_ERR_ARG, "nut, u and out must be 256-byte aligned");
+  return launch_viscous_multiscale(m, nut, u, out, static_cast<hipStream_t>(stream));
+}
+
 int dg_enrichment_active(const dg_mesh* m, int32_t* flags, void* stream) {
   if (!m || !flags) return set_error(DG_ERR_ARG, "mesh/flags is NULL");
   if (m->nenr == 0) return DG_OK;

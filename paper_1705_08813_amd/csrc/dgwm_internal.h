@@ -223,6 +223,10 @@ size_t solve_bytes_mesh(const dg_mesh& m);
 // device data of the hierarchy (levels' heights and diagonals, coarse inverse)
 int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+// eddy viscosity nu_t at every point of the psi tables from the enrichment
+// coefficients of u, and out = A u for the multiscale viscous operator
+int launch_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double beta, double* nut, hipStream_t s);
+int launch_viscous_multiscale(const dg_mesh* m, const double* nut, const double* u, double* out, hipStream_t s);
 // div-div penalty: tau_D per cell from u (tau = true, out: ncell doubles) or out = D u with tau_d
 int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr, double* out,
                   hipStream_t s);

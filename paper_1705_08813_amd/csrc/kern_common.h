@@ -31,6 +31,7 @@ struct MeshDev {
   int geo_stride;
   const double* tauF; // [cell][face]
   int nq_wn;          // wall-normal points of enriched cells (the point layout of their tables)
+  const double* nut;  // eddy viscosity [enr][psi_pts] of the multiscale viscous operator (else nullptr)
   int ops_off;        // offset of the Poisson operator tables (poi_ops) inside tab
 };
 

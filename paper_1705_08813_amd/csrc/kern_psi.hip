@@ -265,12 +265,56 @@ __global__ void psi_kernel(const PsiArgs A) {
   o[3] = dU * st * gyh[2] + dU * dt * gtz;
 }
 
+// Eddy viscosity of the RANS scale (Sec. 2.2) at every point of the psi
+// tables: nu_t = l_mix^2 |eps(u~)| (eq. mix), l_mix = kappa y_DES (1 -
+// exp(-y+/A+)) (eq. lmix), y_DES = y C h / (y^beta + (C h)^beta)^(1/beta), the
+// smooth minimum of eq. ydes written so that it is 0 at the wall, h = dy_e /
+// (k+1).  With l = 0, grad u~ = ut (x) grad psi (ut the cell's enrichment
+// coefficients), |eps| = sqrt(2 eps : eps).  Zero in switched-off cells.
+struct EddyArgs {
+  const double* ut;  // enrichment block of the velocity, [enr][c]
+  double c_des, beta, inv_np;
+  double* nut;
+};
+
+template <int NQ, int NQY>
+__global__ void eddy_kernel(const PsiArgs A, const EddyArgs X) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= A.nenr * A.psi_pts) return;
+  constexpr int PTS = psi_points(NQ, NQY);
+  const int64_t enr = gid / PTS;
+  const int pt = (int)(gid - enr * PTS);
+  if (!A.act[enr]) {
+    X.nut[gid] = 0.0;
+    return;
+  }
+  const CellRef c = enriched_cell(A, enr);
+  const PointRef p = decode_point<NQ, NQY>(pt, A.pts);
+  double gtx, gtz;
+  const double yh = fmax(wall_distance(A, c, p, pt, nullptr), 0.0);
+  const double tw = wall_tau(A, c, p, NQ, gtx, gtz);
+  const double yp = yh * sqrt(tw) / A.nu;
+  const double ch = X.c_des * (A.eta[c.ey + 1] - A.eta[c.ey]) * X.inv_np;
+  const double ydes = yh * ch / pow(pow(yh, X.beta) + pow(ch, X.beta), 1.0 / X.beta);
+  const double lmix = A.kappa * ydes * (1.0 - exp(-yp / A.A_plus));
+  const double* g = A.psi + gid * 4 + 1;
+  const double* ut = X.ut + enr * 3;
+  double e2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double eij = 0.5 * (ut[i] * g[j] + ut[j] * g[i]);
+      e2 += eij * eij;
+    }
+  X.nut[gid] = lmix * lmix * sqrt(2.0 * e2);
+}
+
 }  // namespace
 
 #define DG_PSI_COMBOS(X) X(4, 8) X(4, 4) X(5, 8) X(5, 5) X(7, 8) X(8, 8)
 
-int launch_psi(const dg_mesh* m, hipStream_t s) {
-  if (m->nenr == 0) return DG_OK;
+static PsiArgs psi_args(const dg_mesh* m) {
   PsiArgs A;
   A.nx = m->P.nx;
   A.ny = m->P.ny;
@@ -298,6 +342,12 @@ int launch_psi(const dg_mesh* m, hipStream_t s) {
   A.psi = m->psi;
   A.act = m->act;
   A.vd = m->vd;
+  return A;
+}
+
+int launch_psi(const dg_mesh* m, hipStream_t s) {
+  if (m->nenr == 0) return DG_OK;
+  const PsiArgs A = psi_args(m);
   const int64_t n = m->nenr * m->psi_pts;
   const unsigned nb = (unsigned)((n + 127) / 128);
 #define X(a, b)                                                                            \
@@ -313,6 +363,27 @@ int launch_psi(const dg_mesh* m, hipStream_t s) {
   DG_PSI_COMBOS(X)
 #undef X
   return set_error(DG_ERR_UNSUPPORTED, "psi table: quadrature combination not compiled");
+}
+
+int launch_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double beta, double* nut, hipStream_t s) {
+  if (m->nenr == 0) return DG_OK;
+  const PsiArgs A = psi_args(m);
+  EddyArgs X;
+  X.ut = u + m->ncell * 3 * (int64_t)m->np_u * m->np_u * m->np_u;
+  X.c_des = c_des;
+  X.beta = beta;
+  X.inv_np = 1.0 / m->np_u;
+  X.nut = nut;
+  const int64_t n = m->nenr * m->psi_pts;
+  const unsigned nb = (unsigned)((n + 127) / 128);
+#define X_(a, b)                                                                 \
+  if (m->P.nq_u == a && m->P.nq_wn == b) {                                       \
+    hipLaunchKernelGGL((eddy_kernel<a, b>), dim3(nb), dim3(128), 0, s, A, X);   \
+    return check_hip(hipGetLastError(), "eddy viscosity kernel launch");        \
+  }
+  DG_PSI_COMBOS(X_)
+#undef X_
+  return set_error(DG_ERR_UNSUPPORTED, "eddy viscosity: quadrature combination not compiled");
 }
 
 }  // namespace dgwm

@@ -190,6 +190,107 @@ __device__ __forceinline__ void load_face_tab(const double* tab, T* s_tab) {
   }
 }
 
+// One face point of the multiscale viscous operator (Sec. 4.2, eq.
+// viscous_multiscale; -F^nu_e, adjoint sign -1) in the general face phase.
+// tr holds the polynomial traces of both sides (own: tr[0]; neighbour:
+// tr[1], unset on a wall) in the layout of vel_faces_dir; the enrichment
+// parts u~ = psi ut come from the psi tables.  Face classes: an enriched
+// cell's face is "inner" when its other side is enriched or a wall (mirror
+// side), "interface" otherwise; a cell without enrichment sees "regular" or
+// "interface" faces, which take the same form with the jump of the full
+// velocity.  Writes the weighted value flux, F_g[c][D], F_g[D][T1] and
+// F_g[D][T2] in the vel_faces_dir layout and adds the face terms of the
+// enrichment test rows to rt.
+template <typename T, bool ENR, int D, int T1, int T2>
+__device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr)[2][8], int s, int pt, int FP,
+                                                  bool wall, int64_t enr_nb, int64_t enr, const T* s_ut,
+                                                  const T* s_nut, T wf, T tau, T* fo, T rt[3]) {
+  const T nu = T(M.nu);
+  const T sg = s ? T(1) : T(-1);
+  const int f = 2 * D + s, fn = 2 * D + (1 - s);
+  // normal column of the symmetric polynomial gradient, (grad u + grad u^T)_{cD}
+  auto sym = [&](const T* t, int c) {
+    return c == D ? T(2) * t[3 + D] : (c == T1 ? t[3 + c] + t[6] : t[3 + c] + t[7]);
+  };
+  T ubm[3], ubp[3], sbm[3], sbp[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ubm[c] = tr[0][c];
+    sbm[c] = sym(tr[0], c);
+    ubp[c] = wall ? -ubm[c] : tr[1][c];
+    sbp[c] = wall ? sbm[c] : sym(tr[1], c);
+  }
+  // enrichment parts: u~ = psi ut, (grad u~ + grad u~^T)_{cD} = ut_c dD psi + ut_D dc psi
+  T utm[3] = {0, 0, 0}, stm[3] = {0, 0, 0}, utp[3] = {0, 0, 0}, stp[3] = {0, 0, 0};
+  T psim = 0, gpsim[3] = {0, 0, 0}, num = 0, nup = 0;
+  if (ENR) {
+    const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + f] + pt) * 4;
+    psim = T(ps[0]);
+    gpsim[0] = T(ps[1]);
+    gpsim[1] = T(ps[2]);
+    gpsim[2] = T(ps[3]);
+    num = T(M.nut[(size_t)enr * M.psi_pts + M.psi_off[1 + f] + pt]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      utm[c] = psim * s_ut[c];
+      stm[c] = s_ut[c] * gpsim[D] + s_ut[D] * gpsim[c];
+    }
+  }
+  const bool nb_enr = !wall && enr_nb >= 0;
+  if (wall) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      utp[c] = -utm[c];
+      stp[c] = stm[c];
+    }
+    nup = num;
+  } else if (nb_enr) {
+    const size_t q = (size_t)enr_nb * M.psi_pts + M.psi_off[1 + fn] + pt;
+    const double* ps = M.psi + q * 4;
+    const T psip = T(ps[0]);
+    const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
+    const T* ut = s_nut + f * 3;
+    nup = T(M.nut[q]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      utp[c] = psip * ut[c];
+      stp[c] = ut[c] * gpp[D] + ut[D] * gpp[c];
+    }
+  }
+  const bool inner = ENR && (wall || nb_enr);
+  // harmonic weights of the averages with nu + nu_t (eq. harmweights)
+  const T den = T(2) * nu + num + nup;
+  const T wm = inner ? (nu + nup) / den : T(0.5), wp = inner ? (nu + num) / den : T(0.5);
+  T jb[3], ju[3], Eb[3], Et[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    jb[c] = ubm[c] - ubp[c];
+    ju[c] = (ubm[c] + utm[c]) - (ubp[c] + utp[c]);
+    Eb[c] = T(0.5) * nu * sg * (sbm[c] + sbp[c]);
+    Et[c] = inner ? sg * (wm * (nu + num) * stm[c] + wp * (nu + nup) * stp[c]) : T(0);
+  }
+  const T* J = inner ? jb : ju;
+  const T hn = T(0.5) * nu * sg;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T fv = -Eb[c] - Et[c] + tau * nu * ju[c];
+    fo[c * FP] = wf * fv;
+    fo[(3 + c) * FP] = wf * (c == D ? T(2) : T(1)) * hn * J[c];
+  }
+  fo[6 * FP] = wf * hn * J[T1];
+  fo[7 * FP] = wf * hn * J[T2];
+  if (ENR) {
+    const T gn = sg * gpsim[D];
+    const T jg = ju[0] * gpsim[0] + ju[1] * gpsim[1] + ju[2] * gpsim[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T val = inner ? psim * (-Et[c] + tau * nu * ju[c]) + wm * (nu + num) * (ju[c] * gn + (c == D ? jg * sg : T(0)))
+                          : psim * (-Eb[c] + tau * nu * ju[c]);
+      rt[c] += wf * val;
+    }
+  }
+}
+
 // Both faces of direction D: traces on both sides at the face Gauss points
 // (factorized 2-D interpolation of the node layers), numerical flux, and
 // integration against the cell's own test functions (transposed sweeps).
@@ -202,7 +303,7 @@ __device__ __forceinline__ void load_face_tab(const double* tab, T* s_tab) {
 // Every 1-D contraction runs as a thread-owned line with the table entries
 // as literals of the unrolled code (one LDS read per input, none per
 // coefficient); phases are separated by workgroup barriers.
-template <typename T, int NP, int NQ, int NQY, bool ENR, int D>
+template <typename T, int NP, int NQ, int NQY, bool ENR, int D, bool MS = false>
 __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, const T* s_nl, const T* s_nut, T* s_r,
                                               T* s_face, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
                                               T hy, T hz, T ihx, T ihy, T ihz, T rt[3]) {
@@ -360,6 +461,12 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     if (!wall) {
 #pragma unroll
       for (int f = 0; f < 8; ++f) tr[1][f] = TR[((s * 2 + 1) * 8 + f) * FP + pt];
+    }
+    if constexpr (MS) {
+      vel_ms_face_point<T, ENR, D, T1, T2>(M, tr, s, pt, FP, wall, enr_nb, enr, s_ut, s_nut,
+                                           T(tb1.w[q1]) * T(tb2.w[q2]) * ht1 * ht2, s ? tau1 : tau0, FL + s * 8 * FP + pt,
+                                           rt);
+      continue;
     }
     T psim = 0, gpsim[3] = {0, 0, 0};
     if (ENR) {
@@ -1293,7 +1400,7 @@ __device__ __forceinline__ void vel_cell_affine(const MeshDev& M, const T* __res
 
 // One cell: block-local index b within its launch (regular cells: layer range
 // [layer_lo, layer_lo + nlayers); enriched cells: the enriched index).
-template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED, bool MS = false>
 __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
                                                  int layer_lo, int nlayers) {
   using Sh = VelShape<T, NP, NQ, NQY>;
@@ -1406,6 +1513,36 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
         for (int d = 0; d < 3; ++d) gg[c][d] = s_grad[(c * 3 + d) * NPTS + pt];
       }
     }
+    if constexpr (MS) {
+      // multiscale viscous volume terms (eq. viscous_multiscale): polynomial
+      // tests against 2 nu eps(u_bar) + 2 nuhat eps(u~), nuhat the limited
+      // viscosity of eq. minvt; enrichment tests against 2 (nu + nu_t) eps(u~)
+      T gt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      T gps[3] = {0, 0, 0}, nt = nu, nhat = nu;
+      if (ENR) {
+        const double* ps = M.psi + ((size_t)enr * M.psi_pts + pt) * 4;
+        gps[0] = T(ps[1]);
+        gps[1] = T(ps[2]);
+        gps[2] = T(ps[3]);
+        nt = nu + T(M.nut[(size_t)enr * M.psi_pts + pt]);
+        const T lim = T(2) * sqrt(nu * nt);
+        nhat = nt < lim ? nt : lim;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) gt[c][d] = s_ut[c] * gps[d];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const T st = gt[c][d] + gt[d][c];
+          if (ENR) rt[c] += wq * nt * st * gps[d];
+          s_grad[(c * 3 + d) * NPTS + pt] = wq * (nu * (gg[c][d] + gg[d][c]) + nhat * st);
+        }
+      }
+      continue;
+    }
     T gps[3] = {0, 0, 0};
     if (ENR) {
       const double* ps = M.psi + ((size_t)enr * M.psi_pts + pt) * 4;
@@ -1491,19 +1628,19 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 0>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 0>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 0, MS>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
                                            iz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 1>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 1>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 1, MS>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
                                            iz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 2>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 2>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 2, MS>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
                                            iz, rt);
 
   for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
@@ -1556,6 +1693,17 @@ __global__ __launch_bounds__(256, (vel_wg_per_cu<T, NP, NQ, NQY, ENR, CURVED>())
 }
 
 }  // namespace
+
+// Multiscale viscous operator (FP64, flat cells): the general cell path in
+// its viscous-only mode.
+template <int NP, int NQ, int NQY, bool ENR>
+__global__ __launch_bounds__(256, 3) void visc_ms_kernel(const MeshDev M, const double* __restrict__ u,
+                                                         double* __restrict__ r, int layer_lo, int nlayers) {
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = bid & 7, m8 = bid >> 3;
+  const int blk = xcd * q8 + (xcd < r8 ? xcd : r8) + m8;
+  vel_cell_general<double, NP, NQ, NQY, ENR, false, true>(M, u, r, blk, layer_lo, nlayers);
+}
 
 // One mesh of a batched launch.
 struct VelBatchItem {
@@ -1639,6 +1787,7 @@ MeshDev make_meshdev_u(const dg_mesh* m) {
   M.geo_stride = m->geo_stride;
   M.tauF = m->tauF;
   M.nq_wn = m->P.nq_wn;
+  M.nut = nullptr;
   return M;
 }
 
@@ -1682,6 +1831,30 @@ bool velocity_supported(int np, int nq, int nqy) {
 }
 
 const char* velocity_combos() { return "velocity (k+1, nq_u, nq_wn): (3,4,8) (3,4,4) (4,4,8) (4,5,8) (4,5,5) (5,7,8) (6,8,8)"; }
+
+template <int NP, int NQ, int NQW>
+static int launch_visc_ms_t(const dg_mesh* m, MeshDev M, const double* u, double* r, hipStream_t s) {
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  if (nl > 0)
+    hipLaunchKernelGGL((visc_ms_kernel<NP, NQ, NQ, false>), dim3((unsigned)((int64_t)m->P.nx * nl * m->P.nz)),
+                       dim3(256), 0, s, M, u, r, lo, nl);
+  if (m->nenr > 0)
+    hipLaunchKernelGGL((visc_ms_kernel<NP, NQ, NQW, true>), dim3((unsigned)m->nenr), dim3(256), 0, s, M, u, r, 0, 0);
+  return check_hip(hipGetLastError(), "multiscale viscous kernel launch");
+}
+
+int launch_viscous_multiscale(const dg_mesh* m, const double* nut, const double* u, double* out, hipStream_t s) {
+  MeshDev M = make_meshdev_u(m);
+  M.nut = nut;
+  const int np = m->np_u, nq = m->P.nq_u, nqw = m->P.nq_wn;
+#define X(a, b, c)                                                        \
+  if (np == a && nq == b && (nqw == c || m->nenr == 0)) return launch_visc_ms_t<a, b, c>(m, M, u, out, s);
+  DG_VEL_COMBOS(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "velocity degree/quadrature combination not compiled");
+}
 
 int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s) {
   const MeshDev M = make_meshdev_u(m);
