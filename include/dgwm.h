@@ -383,7 +383,6 @@ typedef struct {
   int32_t max_outer;    /* cap on the FP64 (outer) conjugate-gradient iterations                */
   int32_t max_inner;    /* mixed: FP32 CG iterations per preconditioner call (0: polynomial only)*/
   int32_t cheb_degree;  /* degree of the Jacobi-Chebyshev polynomial preconditioner (>= 1)      */
-  double inner_rtol;    /* reserved (inner iterations run a fixed count, without host syncs)   */
   int32_t mixed;        /* 1: preconditioner in FP32; 0: everything FP64                        */
   int32_t multigrid;    /* 1: the preconditioner is one geometric multigrid V-cycle whose        */
                         /*    smoother is the degree-cheb_degree Jacobi-Chebyshev polynomial;    */

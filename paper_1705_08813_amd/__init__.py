@@ -247,10 +247,10 @@ class Mesh:
         _lib.check(_lib.lib().dg_enrichment_active(self.handle, _dptr(out), _stream_ptr(stream)))
         return out[:self.n_enriched]
 
-    def solve_params(self, rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5, inner_rtol=0.0,
+    def solve_params(self, rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5,
                      multigrid=True, coarse_degree=3):
         return SolveParams(rtol=rtol, max_outer=max_outer, max_inner=max_inner, cheb_degree=cheb_degree,
-                           inner_rtol=inner_rtol, mixed=int(mixed), multigrid=int(multigrid),
+                           mixed=int(mixed), multigrid=int(multigrid),
                            coarse_degree=coarse_degree)
 
     def solve_workspace(self, sp):

@@ -40,7 +40,7 @@ class MeshParams(ctypes.Structure):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
-                ("cheb_degree", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("mixed", ctypes.c_int32),
+                ("cheb_degree", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("multigrid", ctypes.c_int32), ("coarse_degree", ctypes.c_int32)]
 
 

@@ -138,7 +138,7 @@ class Server:
     def _sp(self):
         k = self.solve_kw
         return _lib.SolveParams(rtol=k["rtol"], max_outer=k["max_outer"], max_inner=k["max_inner"],
-                                cheb_degree=k["cheb_degree"], inner_rtol=0.0, mixed=int(k["mixed"]),
+                                cheb_degree=k["cheb_degree"], mixed=int(k["mixed"]),
                                 multigrid=int(k["multigrid"]), coarse_degree=int(k["coarse_degree"]))
 
     # -- worker jobs (run on pool threads, each on its own stream) ---------

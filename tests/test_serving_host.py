@@ -29,7 +29,7 @@ def test_request_stream_is_seeded_and_covers_the_sets():
 
 
 def test_footprint_counts_every_resident_buffer():
-    sp = _lib.SolveParams(rtol=1e-10, max_outer=10, max_inner=0, cheb_degree=5, inner_rtol=0.0, mixed=1)
+    sp = _lib.SolveParams(rtol=1e-10, max_outer=10, max_inner=0, cheb_degree=5, mixed=1)
     for q in serving_requests(ServingConfig(n_requests=16)):
         m = q.workload.mesh
         fp = footprint_bytes(q.workload, sp)
