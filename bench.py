@@ -173,7 +173,10 @@ def main():
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": "channel 64x32x32, tanh 1.8, k_u=4 (7^3 Gauss points, 7x8x7 in 4096 enriched "
                                   "wall cells), k_p=3 (4^3), FP64: psi refresh + velocity residual + SIP Poisson",
-                      "velocity_dofs": n_vel, "pressure_dofs": n_p, "seed": wl.seed},
+                      "velocity_dofs": n_vel, "pressure_dofs": n_p, "seed": wl.seed,
+                      "solve": "extras: SIP Poisson k_p=3 to 1e-10 (true FP64 residual), FP64 flexible CG "
+                               "preconditioned by one geometric-multigrid V-cycle with Jacobi-Chebyshev smoothing "
+                               "(degree 5 fine, 3 coarse) run in FP32 for 'mixed' (no inner CG) or FP64"},
            "roofline": roofline}
     extras = {"psi_ms": t_psi * 1e3, "velocity_ms": t_vel * 1e3, "poisson_ms": t_poi * 1e3,
               "velocity_GBps_alg": BYTES_PER_DOF_F64 * n_vel / t_vel / 1e9,
@@ -210,6 +213,7 @@ def main():
         print("bench: Poisson solves", file=sys.stderr, flush=True)
         # Poisson solve to 1e-10 (same mesh, k=3): mixed precision vs all-FP64
         bsol = torch.tensor(np.random.default_rng(PRESETS["precision"].seed).uniform(-1, 1, n_p), device=dev)
+        xs_by_key = {}
         for mixed in (True, False):
             sp = mesh.solve_params(mixed=mixed)
             ws = mesh.solve_workspace(sp)
@@ -223,12 +227,40 @@ def main():
                 times.append(time.perf_counter() - t_s)
             times = np.sort(np.array(times))
             key = "solve_mixed" if mixed else "solve_f64"
+            xs_by_key[key] = x.cpu().numpy()
             extras[key] = {"median_s": float(np.median(times)), "p50_s": float(np.percentile(times, 50)),
                            "p99_s": float(np.percentile(times, 99)), "outer_its": st.outer_its,
                            "f64_applies": st.op_applies_f64, "f32_applies": st.op_applies_f32,
                            "rel_resid": st.rel_resid, "solves": args.solves,
                            "dofs_per_s": n_p / float(np.median(times))}
         extras["solve_speedup_mixed_vs_f64"] = extras["solve_f64"]["median_s"] / extras["solve_mixed"]["median_s"]
+        # Jacobi-preconditioned FP64 CG to 1e-10 (Chebyshev degree 1 is a multiple of Jacobi, so CG takes the
+        # Jacobi-PCG iterations): its iteration count times the oracle's cost per iteration is the CPU
+        # oracle's solve time
+        spj = mesh.solve_params(mixed=False, multigrid=False, cheb_degree=1, max_outer=40000)
+        _, stj = mesh.solve_poisson(bsol, sp=spj, workspace=mesh.solve_workspace(spj))
+        extras["solve_jacobi_cg_f64"] = {"outer_its": stj.outer_its, "rel_resid": stj.rel_resid,
+                                         "seconds": stj.seconds}
+        if not args.no_cpu_baseline:
+            import oracle as O
+            print("bench: oracle residuals of the solutions", file=sys.stderr, flush=True)
+            bnp = bsol.cpu().numpy()
+            bp = bnp - bnp.mean()
+            for key, xs in xs_by_key.items():
+                res = bp - O.poisson_apply(m, xs)
+                extras[key]["oracle_rel_resid"] = float(np.linalg.norm(res) / np.linalg.norm(bp))
+            t_o = time.perf_counter()
+            napp = 2
+            for _ in range(napp):
+                O.poisson_apply(m, bp)
+            t_it = (time.perf_counter() - t_o) / napp
+            extras["cpu_oracle_solve_f64"] = {
+                "kind": "oracle", "cores": O.num_threads(), "method": "Jacobi-preconditioned FP64 CG to 1e-10",
+                "iterations": stj.outer_its, "seconds_per_iteration": t_it,
+                "estimated_seconds": stj.outer_its * t_it,
+                "sample": f"{napp} oracle Poisson applies on the full {m.ncell}-cell mesh timed; the iteration count "
+                          "is that of the same Jacobi-preconditioned CG run on the GPU (identical in exact "
+                          "arithmetic), vector updates not counted"}
     if not args.no_extras:
         # van Driest enrichment (eq. psi, Appendix A evaluation) on the same mesh: psi refresh and
         # velocity residual (the residual kernel is the same; only the psi tables differ)
@@ -371,8 +403,8 @@ def main():
         t_dd = ev7[1].elapsed_time(ev7[2]) / nrep
         extras["divdiv"] = {"tau_ms": ev7[0].elapsed_time(ev7[1]) / nrep, "apply_ms": t_dd,
                             "apply_GBps_alg": 16.0 * n_vel / (t_dd * 1e-3) / 1e9}
-        # element-wise projection step (M + D) x = M u_hat - dt P p, per-cell PCG to 1e-14:
-        # u_hat, P p in, x out (24 B per unknown); the cost is the per-cell iterations
+        # element-wise projection step (M + D) x = M u_hat - dt P p, a direct solve per cell (per-layer
+        # eigenbasis, bordered in enriched cells): u_hat, P p in, x out (24 B per unknown)
         mesh.apply_pressure_gradient(p, gv)
         xs = torch.empty_like(u)
         for _ in range(2):
@@ -387,6 +419,33 @@ def main():
         t_ps = ev8[0].elapsed_time(ev8[1]) / nps
         extras["projection_step"] = {"ms": t_ps, "GBps_alg": 24.0 * n_vel / (t_ps * 1e-3) / 1e9}
         del gv, cp, td, xs
+    if not args.no_extras:
+        # multiscale viscous operator (Sec. 4.2, eq. viscous_multiscale) with the eddy viscosity of Sec. 2.2,
+        # on the same mesh with tau_w scaled by 1600 (wall cells at y+ ~ 70-120, nu_t up to tens of nu)
+        print("bench: multiscale viscous operator", file=sys.stderr, flush=True)
+        msm = Mesh(m, 1600.0 * inp["tau"], device=dev)
+        nut = msm.eddy_viscosity(u)
+        ov = torch.empty_like(u)
+        for _ in range(3):
+            msm.eddy_viscosity(u, nut=nut)
+            msm.apply_viscous_multiscale(nut, u, ov)
+        ev9 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        nrep = max(10, K)
+        ev9[0].record(stream)
+        for _ in range(nrep):
+            msm.eddy_viscosity(u, nut=nut)
+        ev9[1].record(stream)
+        for _ in range(nrep):
+            msm.apply_viscous_multiscale(nut, u, ov)
+        ev9[2].record(stream)
+        torch.cuda.synchronize()
+        t_ms = ev9[1].elapsed_time(ev9[2]) / nrep
+        ms_bytes = 16.0 * n_vel + 8.0 * nut.numel()
+        extras["viscous_multiscale"] = {"eddy_viscosity_ms": ev9[0].elapsed_time(ev9[1]) / nrep,
+                                        "nu_t_points": int(nut.numel()), "apply_ms": t_ms,
+                                        "apply_dofs_per_s": n_vel / (t_ms * 1e-3),
+                                        "apply_GBps_alg": ms_bytes / (t_ms * 1e-3) / 1e9}
+        del msm, nut, ov
     if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)
