@@ -376,6 +376,36 @@ int dg_apply_poisson(const dg_mesh* mesh, dg_prec prec, const void* p, void* y, 
  * device vector d (dg_num_dofs(mesh, 1) doubles). */
 int dg_poisson_diagonal(const dg_mesh* mesh, double* d, void* stream);
 
+/* Levels of the geometric multigrid hierarchy of the pressure space (the
+ * preconditioner of dg_solve_poisson with multigrid = 1; Sec. 4.4 names
+ * multigrid-preconditioned CG as the paper's pressure solver).  Level 0 is
+ * the mesh; level l+1 merges cell pairs of level l along every direction
+ * with an even cell count (y only while at least 4 layers remain, 2 when
+ * fully periodic) until the dense coarse solve is small enough.  Writes six
+ * int32 per level for the first min(levels, cap) levels: nx, ny, nz, cx,
+ * cy, cz (cx, cy, cz = 1 where level l was coarsened from l-1 along x, y, z;
+ * zero on level 0).  out may be NULL when cap is 0.  Returns the number of
+ * levels (0 on curved meshes, which have no hierarchy) or a negative error
+ * code. */
+int dg_mg_levels(const dg_mesh* mesh, int32_t* out, int32_t cap);
+
+/* One transfer between levels l and l+1 of that hierarchy, queued on
+ * stream.  The prolongation P is the exact embedding of the level-(l+1) DG
+ * space into the level-l one: nodal values of each coarse-cell polynomial
+ * at the Gauss-Lobatto nodes of its 2, 4 or 8 child cells (a y pair split
+ * at the ratio of the two layer heights).  Vectors use the pressure layout
+ * of the level (cells x fastest, then y, z; nodes (k_p+1)^3 per cell, x
+ * fastest).
+ *   direction 0 (restriction): out = P^T in; in: level l, out: level l+1.
+ *   direction 1 (prolongation): out = add + P in; in: level l+1, add and
+ *     out: level l (add may equal out; pass a zero vector to get P in).
+ *   prec: DG_F64 -> double vectors, DG_F32 -> float.  in must not alias out.
+ * Errors: DG_ERR_ARG for a level outside 0 .. levels-2, an unknown
+ * direction or precision, or NULL pointers; DG_ERR_UNSUPPORTED on curved
+ * meshes. */
+int dg_mg_transfer(const dg_mesh* mesh, int32_t level, int32_t direction, dg_prec prec, const void* in,
+                   const void* add, void* out, void* stream);
+
 /* ---------------------------------------------------------------- solve --- */
 
 typedef struct {

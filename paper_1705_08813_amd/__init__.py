@@ -95,6 +95,41 @@ class Mesh:
         _lib.check(_lib.lib().dg_poisson_diagonal(self.handle, _dptr(d), _stream_ptr(stream)))
         return d
 
+    def mg_levels(self):
+        """dg_mg_levels: [(nx, ny, nz, cx, cy, cz)] of every multigrid level."""
+        n = _lib.check(_lib.lib().dg_mg_levels(self.handle, None, 0))
+        buf = (ctypes.c_int32 * (6 * max(n, 1)))()
+        _lib.check(_lib.lib().dg_mg_levels(self.handle, buf, n))
+        return [tuple(buf[6 * l:6 * l + 6]) for l in range(n)]
+
+    def mg_transfer(self, level, direction, x, add=None, out=None, stream=None):
+        """dg_mg_transfer: direction 0 restricts x (level `level`) to level
+        level+1; direction 1 prolongs x (level level+1) and adds `add`
+        (zeros when None) on level `level`.  float64 or float32 tensors."""
+        import torch
+        lv = self.mg_levels()
+        if not 0 <= level < len(lv) - 1:
+            raise ValueError("level outside the hierarchy")
+        np3 = (self.cfg.k_p + 1) ** 3
+        nf = lv[level][0] * lv[level][1] * lv[level][2] * np3
+        nc = lv[level + 1][0] * lv[level + 1][1] * lv[level + 1][2] * np3
+        n_in, n_out = (nf, nc) if direction == 0 else (nc, nf)
+        if x.dtype not in (torch.float64, torch.float32):
+            raise ValueError("x must be float64 or float32")
+        prec = 0 if x.dtype == torch.float64 else 1
+        for t, n, name in ((x, n_in, "x"), (add, n_out, "add"), (out, n_out, "out")):
+            if t is not None and (t.dtype != x.dtype or t.device != self.device or not t.is_contiguous()
+                                  or t.numel() != n):
+                raise ValueError(f"{name} must be a contiguous {x.dtype} tensor of {n} entries on {self.device}")
+        if out is None:
+            out = torch.empty(n_out, dtype=x.dtype, device=self.device)
+        if direction == 1 and add is None:
+            add = torch.zeros(n_out, dtype=x.dtype, device=self.device)
+        _lib.check(_lib.lib().dg_mg_transfer(self.handle, level, direction, prec, _dptr(x),
+                                             _dptr(add) if add is not None else None, _dptr(out),
+                                             _stream_ptr(stream)))
+        return out
+
     def _check_f64(self, t, n, name):
         import torch
         if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device \

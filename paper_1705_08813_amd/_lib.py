@@ -80,6 +80,8 @@ _SIGS = {
                                                           ctypes.c_size_t, _VP]),
     "dg_apply_poisson": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "dg_poisson_diagonal": (ctypes.c_int, [_VP, _VP, _VP]),
+    "dg_mg_levels": (ctypes.c_int, [_VP, _VP, ctypes.c_int32]),
+    "dg_mg_transfer": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP, _VP]),
     "dg_solve_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.POINTER(SolveParams)]),
     "dg_solve_workspace_bytes_for": (ctypes.c_int64, [ctypes.POINTER(MeshParams), ctypes.POINTER(SolveParams)]),
     "dg_solve_poisson": (ctypes.c_int, [_VP, ctypes.POINTER(SolveParams), _VP, _VP, _VP, ctypes.c_size_t,

@@ -557,6 +557,30 @@ int dg_apply_poisson(const dg_mesh* m, dg_prec prec, const void* p, void* y, voi
   return launch_poisson(m, prec, p, y, static_cast<hipStream_t>(stream));
 }
 
+int dg_mg_levels(const dg_mesh* m, int32_t* out, int32_t cap) {
+  if (!m) return set_error(DG_ERR_ARG, "mesh is NULL");
+  if (cap < 0 || (cap > 0 && !out)) return set_error(DG_ERR_ARG, "out is NULL or cap negative");
+  for (int l = 0; l < m->mg_nlev && l < cap; ++l) {
+    const MgLevel& v = m->mg[l];
+    const int32_t row[6] = {v.nx, v.ny, v.nz, v.cx, v.cy, v.cz};
+    for (int i = 0; i < 6; ++i) out[6 * l + i] = row[i];
+  }
+  return m->mg_nlev;
+}
+
+int dg_mg_transfer(const dg_mesh* m, int32_t level, int32_t direction, dg_prec prec, const void* in,
+                   const void* add, void* out, void* stream) {
+  if (!m || !in || !out || (direction == 1 && !add)) return set_error(DG_ERR_ARG, "mesh/in/add/out is NULL");
+  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "curved meshes have no multigrid hierarchy");
+  if (level < 0 || level + 1 >= m->mg_nlev) return set_error(DG_ERR_ARG, "level outside the hierarchy");
+  if (prec != DG_F64 && prec != DG_F32) return set_error(DG_ERR_ARG, "unknown precision");
+  if (in == out) return set_error(DG_ERR_ARG, "in and out must not alias");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (direction == 0) return launch_mg_restrict(m, level, prec, in, out, s);
+  if (direction == 1) return launch_mg_prolong_add(m, level, prec, in, add, out, s);
+  return set_error(DG_ERR_ARG, "unknown transfer direction");
+}
+
 int dg_poisson_diagonal(const dg_mesh* m, double* d, void* stream) {
   if (!m || !d) return set_error(DG_ERR_ARG, "mesh/d is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Poisson operator is built for flat (box) meshes only");
