@@ -483,6 +483,44 @@ int dg_solve_poisson(const dg_mesh* mesh, const dg_solve_params* sp, const doubl
 int dg_solve_poisson_noalloc(const dg_mesh* mesh, const dg_solve_params* sp, const double* b, double* x,
                              dg_solve_stats* stats, void* stream);
 
+/* Device bytes of the descriptor workspace of a batched solve over these
+ * n meshes with these parameters, or a negative DG_ERR_* code. */
+int64_t dg_solve_batch_workspace_bytes(const dg_mesh* const* meshes, int32_t n, const dg_solve_params* sp);
+
+/* The solves of n independent meshes (the serving path: one pressure step,
+ * Sec. 4.1 eq. poisson, per wall-modelled channel) advanced together: every
+ * outer iteration of every unconverged mesh runs in the same launches, one
+ * per step of the iteration and degree group (operator applications and
+ * fused Chebyshev steps of every multigrid level, transfers, coarse solves,
+ * vector updates and reductions), from descriptor tables kept in batch_ws
+ * while the set of unconverged meshes is unchanged.  A mesh leaves the batch
+ * when it converges.  Per mesh the method and the stopping rule are those of
+ * dg_solve_poisson with multigrid = 1, and its arithmetic does not depend on
+ * the other meshes of the batch: a mesh gives bit-for-bit the same x and
+ * statistics in any batch, alone included (reductions use a block count set
+ * by the vector length; results may differ from dg_solve_poisson's in the
+ * last bits).  Eigenvalue estimates missing from a mesh's cache are computed
+ * for all such meshes together at the start.  One host read-back per outer
+ * iteration for the whole batch, through pinned memory owned by the calling
+ * thread (allocated on its first call and kept for the thread's lifetime).
+ *   meshes, b, x, ws, ws_bytes: host arrays of n entries; b[i], x[i] device
+ *     vectors of dg_num_dofs(meshes[i], 1) doubles (x[i] holds the initial
+ *     guess), ws[i] a workspace of ws_bytes[i] >= dg_solve_workspace_bytes
+ *     bytes, all pairwise distinct;
+ *   sp: shared parameters (multigrid must be 1);
+ *   stats, codes: host arrays of n entries (may be NULL): per mesh
+ *     statistics and status (DG_OK, DG_ERR_NOT_CONVERGED, DG_ERR_NONFINITE);
+ *   batch_ws: device, >= dg_solve_batch_workspace_bytes(meshes, n, sp).
+ * Returns DG_OK when the batch ran (per mesh outcomes in codes), else
+ * DG_ERR_ARG, DG_ERR_WORKSPACE, DG_ERR_UNSUPPORTED (multigrid = 0, a curved
+ * mesh or one without a coarser level) or DG_ERR_HIP.  Calls on one thread
+ * must not overlap (they share its pinned staging); the call returns after
+ * the stream has drained. */
+int dg_solve_poisson_batched(const dg_mesh* const* meshes, int32_t n, const dg_solve_params* sp,
+                             const double* const* b, double* const* x, void* const* ws, const size_t* ws_bytes,
+                             dg_solve_stats* stats, int32_t* codes, void* batch_ws, size_t batch_ws_bytes,
+                             void* stream);
+
 /* ---------------------------------------------------------------- misc --- */
 
 const char* dg_last_error(void);

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import DG_F32, DG_F64, DgError, SolveParams, SolveStats
 
 __all__ = ["Mesh", "DgError", "DG_F64", "DG_F32", "SolveParams", "SolveStats", "apply_velocity_residual_batched",
-           "batch_workspace"]
+           "batch_workspace", "solve_poisson_batched", "solve_batch_workspace"]
 
 
 def _stream_ptr(stream):
@@ -345,6 +345,49 @@ def batch_workspace(n, device=None):
     nbytes = _lib.check(_lib.lib().dg_batch_workspace_bytes(int(n)))
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+
+
+def solve_batch_workspace(meshes, sp):
+    """Device descriptor workspace of a batched solve over these meshes."""
+    import torch
+    n = len(meshes)
+    hs = (ctypes.c_void_p * n)(*[m.handle.value for m in meshes])
+    nbytes = _lib.check(_lib.lib().dg_solve_batch_workspace_bytes(hs, n, ctypes.byref(sp)))
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=meshes[0].device)
+
+
+def solve_poisson_batched(meshes, bs, xs=None, sp=None, workspaces=None, batch_ws=None, stream=None):
+    """dg_solve_poisson_batched: the solves of every mesh of the list
+    advanced together.  Returns (xs, stats, codes): per mesh solution,
+    SolveStats and status code (0 = converged)."""
+    import torch
+    n = len(meshes)
+    if n == 0 or len(bs) != n or (xs is not None and len(xs) != n):
+        raise ValueError("meshes, bs and xs must be non-empty lists of one length")
+    if sp is None:
+        sp = meshes[0].solve_params()
+    if xs is None:
+        xs = [torch.zeros_like(b) for b in bs]
+    for m, b, x in zip(meshes, bs, xs):
+        if b.dtype != torch.float64 or x.dtype != torch.float64:
+            raise ValueError("b and x must be float64")
+        m._check_vec(b, m.n_p, "b")
+        m._check_vec(x, m.n_p, "x")
+    if workspaces is None:
+        workspaces = [m.solve_workspace(sp) for m in meshes]
+    if batch_ws is None:
+        batch_ws = solve_batch_workspace(meshes, sp)
+    VP = ctypes.c_void_p
+    hs = (VP * n)(*[m.handle.value for m in meshes])
+    bp = (VP * n)(*[b.data_ptr() for b in bs])
+    xp = (VP * n)(*[x.data_ptr() for x in xs])
+    wp = (VP * n)(*[w.data_ptr() for w in workspaces])
+    wb = (ctypes.c_size_t * n)(*[w.numel() for w in workspaces])
+    stats = (SolveStats * n)()
+    codes = (ctypes.c_int32 * n)()
+    _lib.check(_lib.lib().dg_solve_poisson_batched(hs, n, ctypes.byref(sp), bp, xp, wp, wb, stats, codes,
+                                                   _dptr(batch_ws), batch_ws.numel(), _stream_ptr(stream)))
+    return xs, list(stats), list(codes)
 
 
 def apply_velocity_residual_batched(meshes, us, rs=None, workspace=None, stream=None):

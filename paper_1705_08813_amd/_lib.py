@@ -88,6 +88,12 @@ _SIGS = {
                                         ctypes.POINTER(SolveStats), _VP]),
     "dg_solve_poisson_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(SolveParams), _VP, _VP,
                                                 ctypes.POINTER(SolveStats), _VP]),
+    "dg_solve_batch_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(_VP), ctypes.c_int32,
+                                                       ctypes.POINTER(SolveParams)]),
+    "dg_solve_poisson_batched": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int32, ctypes.POINTER(SolveParams),
+                                                ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                                ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(SolveStats),
+                                                ctypes.POINTER(ctypes.c_int32), _VP, ctypes.c_size_t, _VP]),
     "dg_last_error": (ctypes.c_char_p, []),
     "dg_build_info": (ctypes.c_char_p, []),
 }

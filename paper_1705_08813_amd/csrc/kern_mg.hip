@@ -14,7 +14,7 @@
 #include <cmath>
 #include <vector>
 
-#include "kern_common.h"
+#include "batch.h"
 
 namespace dgwm {
 
@@ -69,22 +69,15 @@ __device__ __forceinline__ void build_transfer_tables(T* P, int cx, int cy, int 
   }
 }
 
-struct Tr {
-  int nfx, nfy, nfz;   // fine level size
-  int ncx, ncy, ncz;   // coarse level size
-  int cx, cy, cz;
-  const double* hyf;   // fine heights
-};
-
 // rc = P^T rf on one coarse cell
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void mg_restrict_kernel(const Tr tr, const T* __restrict__ rf, T* __restrict__ rc) {
+__device__ __forceinline__ void mg_restrict_body(const Tr& tr, int64_t C, const T* __restrict__ rf,
+                                                 T* __restrict__ rc) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
   __shared__ T P[3 * 2 * NP * NP];
   __shared__ T F[8 * NP3];  // [c][b][a][k][j][l]
   __shared__ T G[4 * NP3];  // [c][b][k][j][i]
   __shared__ T H[2 * NP3];  // [c][k][jc][i]
-  const int64_t C = blockIdx.x;
   const int X = (int)(C % tr.ncx), Y = (int)((C / tr.ncx) % tr.ncy), Z = (int)(C / ((int64_t)tr.ncx * tr.ncy));
   const int na = 1 + tr.cx, nb = 1 + tr.cy, nc = 1 + tr.cz;
   const double ry = tr.cy ? tr.hyf[2 * Y] / (tr.hyf[2 * Y] + tr.hyf[2 * Y + 1]) : 0.5;
@@ -141,13 +134,13 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(const Tr tr, const T* 
 // xo = xf + P xc on the fine cells of one coarse cell (xo may be xf: each
 // entry is read and written by the same thread)
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* __restrict__ xc, const T* xf, T* xo) {
+__device__ __forceinline__ void mg_prolong_body(const Tr& tr, int64_t C, const T* __restrict__ xc, const T* xf,
+                                                T* xo) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
   __shared__ T P[3 * 2 * NP * NP];
   __shared__ T S[NP3];      // [kc][jc][i]
   __shared__ T A[2 * NP3];  // [c][n][jc][i]
   __shared__ T B[4 * NP3];  // [c][b][n][m][i]
-  const int64_t C = blockIdx.x;
   const int X = (int)(C % tr.ncx), Y = (int)((C / tr.ncx) % tr.ncy), Z = (int)(C / ((int64_t)tr.ncx * tr.ncy));
   const int na = 1 + tr.cx, nb = 1 + tr.cy, nc = 1 + tr.cz;
   const double ry = tr.cy ? tr.hyf[2 * Y] / (tr.hyf[2 * Y] + tr.hyf[2 * Y + 1]) : 0.5;
@@ -262,8 +255,8 @@ __device__ __forceinline__ void child_offsets(int64_t* off, const Tr& tr, int64_
 
 // rc = P^T rf
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void mg_restrict_full(const Tr tr, int64_t ncc, const T* __restrict__ rf,
-                                                        T* __restrict__ rc) {
+__device__ __forceinline__ void mg_restrict_full_body(const Tr& tr, int64_t ncc, int64_t blk,
+                                                      const T* __restrict__ rf, T* __restrict__ rc) {
   using F = Full<NP>;
   constexpr int NP2 = F::NP2, NP3 = F::NP3, CPC = F::CPC;
   __shared__ T sF[CPC * 8 * NP3];  // [cc][c][b][a][k][j][l]
@@ -271,7 +264,7 @@ __global__ __launch_bounds__(256) void mg_restrict_full(const Tr tr, int64_t ncc
   __shared__ T sH[CPC * 2 * NP3];  // [cc][c][k][jc][i]
   __shared__ T sPy[CPC * 2 * NP2];
   __shared__ int64_t sOff[CPC * 8];
-  const int64_t C0 = (int64_t)blockIdx.x * CPC;
+  const int64_t C0 = blk * CPC;
   build_py<T, NP>(sPy, tr, C0, ncc);
   child_offsets<NP>(sOff, tr, C0, ncc);
   __syncthreads();
@@ -349,8 +342,8 @@ __global__ __launch_bounds__(256) void mg_restrict_full(const Tr tr, int64_t ncc
 
 // xo = xf + P xc (xo may be xf: each entry is read and written by the same thread)
 template <typename T, int NP>
-__global__ __launch_bounds__(256) void mg_prolong_full(const Tr tr, int64_t ncc, const T* __restrict__ xc,
-                                                       const T* xf, T* xo) {
+__device__ __forceinline__ void mg_prolong_full_body(const Tr& tr, int64_t ncc, int64_t blk,
+                                                     const T* __restrict__ xc, const T* xf, T* xo) {
   using F = Full<NP>;
   constexpr int NP2 = F::NP2, NP3 = F::NP3, CPC = F::CPC;
   __shared__ T sS[CPC * NP3];      // [cc][kc][jc][i]
@@ -359,7 +352,7 @@ __global__ __launch_bounds__(256) void mg_prolong_full(const Tr tr, int64_t ncc,
   __shared__ T sF[CPC * 8 * NP3];  // [cc][c][b][a][n][m][l]
   __shared__ T sPy[CPC * 2 * NP2];
   __shared__ int64_t sOff[CPC * 8];
-  const int64_t C0 = (int64_t)blockIdx.x * CPC;
+  const int64_t C0 = blk * CPC;
   build_py<T, NP>(sPy, tr, C0, ncc);
   child_offsets<NP>(sOff, tr, C0, ncc);
   for (int t = threadIdx.x; t < CPC * NP3; t += blockDim.x) {
@@ -435,10 +428,10 @@ __global__ __launch_bounds__(256) void mg_prolong_full(const Tr tr, int64_t ncc,
 // per lane and a butterfly reduction over the wavefront; four rows per
 // workgroup, so n / 4 workgroups share the matrix read.
 template <typename T>
-__global__ __launch_bounds__(256) void dense_apply_kernel(int n, const T* __restrict__ B, const T* __restrict__ b,
-                                                          T* __restrict__ x) {
+__device__ __forceinline__ void dense_apply_body(int n, int64_t blk, const T* __restrict__ B, const T* __restrict__ b,
+                                                 T* __restrict__ x) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i = (int)blk * 4 + (threadIdx.x >> 6);
   if (i >= n) return;  // whole wavefronts leave together
   const T* row = B + (int64_t)i * n;
   T s0 = 0, s1 = 0;
@@ -454,6 +447,53 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(int n, const T* __rest
   if (lane == 0) x[i] = v;
 }
 
+// Single-mesh kernels (one coarse cell, or CPC coarse cells, per workgroup)
+// and their batched forms over many meshes (segment lookup per workgroup).
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_restrict_kernel(const Tr tr, const T* __restrict__ rf, T* __restrict__ rc) {
+  mg_restrict_body<T, NP>(tr, (int64_t)blockIdx.x, rf, rc);
+}
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_prolong_kernel(const Tr tr, const T* __restrict__ xc, const T* xf, T* xo) {
+  mg_prolong_body<T, NP>(tr, (int64_t)blockIdx.x, xc, xf, xo);
+}
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_restrict_full(const Tr tr, int64_t ncc, const T* __restrict__ rf,
+                                                        T* __restrict__ rc) {
+  mg_restrict_full_body<T, NP>(tr, ncc, (int64_t)blockIdx.x, rf, rc);
+}
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void mg_prolong_full(const Tr tr, int64_t ncc, const T* __restrict__ xc,
+                                                       const T* xf, T* xo) {
+  mg_prolong_full_body<T, NP>(tr, ncc, (int64_t)blockIdx.x, xc, xf, xo);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void dense_apply_kernel(int n, const T* __restrict__ B, const T* __restrict__ b,
+                                                          T* __restrict__ x) {
+  dense_apply_body<T>(n, (int64_t)blockIdx.x, B, b, x);
+}
+
+template <typename T, int NP, bool FULL, bool RESTRICT>
+__global__ __launch_bounds__(256) void mg_transfer_batched(const TrSeg<T>* __restrict__ segs, int nseg) {
+  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
+  const TrSeg<T>& S = segs[si];
+  const int64_t blk = (int64_t)blockIdx.x - S.blk0;
+  if (FULL) {
+    if (RESTRICT) mg_restrict_full_body<T, NP>(S.tr, S.ncc, blk, S.in, S.out);
+    else mg_prolong_full_body<T, NP>(S.tr, S.ncc, blk, S.in, S.add, S.out);
+  } else {
+    if (RESTRICT) mg_restrict_body<T, NP>(S.tr, blk, S.in, S.out);
+    else mg_prolong_body<T, NP>(S.tr, blk, S.in, S.add, S.out);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void dense_apply_batched(const DenseSeg<T>* __restrict__ segs, int nseg) {
+  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
+  const DenseSeg<T>& S = segs[si];
+  dense_apply_body<T>((int)S.n, (int64_t)blockIdx.x - S.blk0, S.B, S.b, S.x);
+}
+
 // columns of the n x n identity, one vector of n entries per column
 __global__ void identity_kernel(double* __restrict__ E, int64_t n) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n * n; t += (int64_t)gridDim.x * blockDim.x)
@@ -465,7 +505,9 @@ __global__ void to_f32_kernel(float* __restrict__ o, const double* __restrict__ 
     o[t] = (float)a[t];
 }
 
-Tr make_tr(const dg_mesh* m, int l) {
+}  // namespace
+
+Tr mg_transfer_geometry(const dg_mesh* m, int l) {
   const MgLevel& f = m->mg[l];
   const MgLevel& c = m->mg[l + 1];
   Tr t;
@@ -482,16 +524,73 @@ Tr make_tr(const dg_mesh* m, int l) {
   return t;
 }
 
-}  // namespace
-
 #define DG_MG_NP(X) X(2) X(3) X(4) X(5) X(6)
 
+bool mg_full_transfer(const dg_mesh* m, int l) {
+  const MgLevel& c = m->mg[l + 1];
+  return c.cx && c.cy && c.cz && c.ncell >= kFullMinCells;
+}
+
+int mg_cells_per_block(int np, bool full) {
+  if (!full) return 1;
+#define X(a) \
+  if (np == a) return Full<a>::CPC;
+  DG_MG_NP(X)
+#undef X
+  return 0;
+}
+
+int dense_rows_per_block() { return 4; }
+
+template <typename T>
+static int launch_mg_batched(int np, bool full, bool restrict_, const TrSeg<T>* segs, int nseg, int64_t nblk,
+                             hipStream_t s) {
+  if (nseg <= 0 || nblk <= 0) return DG_OK;
+#define X(a)                                                                                                   \
+  if (np == a) {                                                                                               \
+    const dim3 g((unsigned)nblk);                                                                              \
+    if (full && restrict_)                                                                                     \
+      hipLaunchKernelGGL((mg_transfer_batched<T, a, true, true>), g, dim3(256), 0, s, segs, nseg);              \
+    else if (full)                                                                                             \
+      hipLaunchKernelGGL((mg_transfer_batched<T, a, true, false>), g, dim3(256), 0, s, segs, nseg);             \
+    else if (restrict_)                                                                                        \
+      hipLaunchKernelGGL((mg_transfer_batched<T, a, false, true>), g, dim3(256), 0, s, segs, nseg);             \
+    else                                                                                                       \
+      hipLaunchKernelGGL((mg_transfer_batched<T, a, false, false>), g, dim3(256), 0, s, segs, nseg);            \
+    return check_hip(hipGetLastError(), "batched transfer launch");                                            \
+  }
+  DG_MG_NP(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "multigrid transfer degree not compiled");
+}
+
+template <typename T>
+int launch_mg_restrict_batched(int np, bool full, const TrSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
+  return launch_mg_batched<T>(np, full, true, segs, nseg, nblk, s);
+}
+template <typename T>
+int launch_mg_prolong_batched(int np, bool full, const TrSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
+  return launch_mg_batched<T>(np, full, false, segs, nseg, nblk, s);
+}
+template <typename T>
+int launch_dense_batched(const DenseSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
+  if (nseg <= 0 || nblk <= 0) return DG_OK;
+  hipLaunchKernelGGL((dense_apply_batched<T>), dim3((unsigned)nblk), dim3(256), 0, s, segs, nseg);
+  return check_hip(hipGetLastError(), "batched dense apply launch");
+}
+template int launch_mg_restrict_batched<double>(int, bool, const TrSeg<double>*, int, int64_t, hipStream_t);
+template int launch_mg_restrict_batched<float>(int, bool, const TrSeg<float>*, int, int64_t, hipStream_t);
+template int launch_mg_prolong_batched<double>(int, bool, const TrSeg<double>*, int, int64_t, hipStream_t);
+template int launch_mg_prolong_batched<float>(int, bool, const TrSeg<float>*, int, int64_t, hipStream_t);
+template int launch_dense_batched<double>(const DenseSeg<double>*, int, int64_t, hipStream_t);
+template int launch_dense_batched<float>(const DenseSeg<float>*, int, int64_t, hipStream_t);
+
 int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s) {
-  const Tr tr = make_tr(m, l);
+  const Tr tr = mg_transfer_geometry(m, l);
   const int64_t ncc = m->mg[l + 1].ncell;
   const unsigned nb = (unsigned)ncc;
   // small levels are latency-bound: one workgroup per coarse cell finishes sooner there
-  const bool full = tr.cx && tr.cy && tr.cz && ncc >= kFullMinCells;
+  const bool full = mg_full_transfer(m, l);
 #define X(a)                                                                                                  \
   if (m->np_p == a && full) {                                                                                 \
     const unsigned g = (unsigned)((ncc + Full<a>::CPC - 1) / Full<a>::CPC);                                   \
@@ -522,11 +621,11 @@ int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, vo
 
 int launch_mg_prolong_add(const dg_mesh* m, int l, dg_prec prec, const void* xc, const void* xf, void* xo,
                           hipStream_t s) {
-  const Tr tr = make_tr(m, l);
+  const Tr tr = mg_transfer_geometry(m, l);
   const int64_t ncc = m->mg[l + 1].ncell;
   const unsigned nb = (unsigned)ncc;
   // small levels are latency-bound: one workgroup per coarse cell finishes sooner there
-  const bool full = tr.cx && tr.cy && tr.cz && ncc >= kFullMinCells;
+  const bool full = mg_full_transfer(m, l);
 #define X(a)                                                                                                  \
   if (m->np_p == a && full) {                                                                                 \
     const unsigned g = (unsigned)((ncc + Full<a>::CPC - 1) / Full<a>::CPC);                                   \

@@ -7,7 +7,7 @@
 // One workgroup per cell, sum-factorized volume term, element-by-element
 // face terms (each cell reads its neighbour's nodal values), single writer
 // per output entry.
-#include "kern_common.h"
+#include "batch.h"
 
 namespace dgwm {
 
@@ -25,27 +25,6 @@ __device__ __forceinline__ int poi_nb(const MeshDev& M, int e, int ex, int ey, i
   }
   return S ? e + step : e - step;
 }
-
-// What the kernel does with y = A p at each output entry (solver fusion):
-//   kPlain: y = A p
-//   kResid: r = b - A p
-//   kCheb:  v = c1 (p - zprev) + c2 dinv (b - A p), zout = p + v: one step
-//           of the Chebyshev recurrence, whose previous iterate zprev is read
-//           from zout before it is overwritten (c1 = 0: not read); zout must
-//           not alias p
-//   kChebFirst: the same step from the first iterate p = c0 dinv b (zprev =
-//           0), which the kernel forms from b as it loads it (the input
-//           pointer is b); p itself is written to z1 for the next step
-enum PoiEpiKind { kPlain = 0, kResid = 1, kCheb = 2, kChebFirst = 3 };
-template <typename T>
-struct PoiEpi {
-  int kind;
-  const T* b;
-  const T* dinv;
-  T* z1;
-  T* zout;
-  T c1, c2, c0;
-};
 
 // Cells per workgroup: one thread per pencil (line of NP nodes), so a cell
 // uses NP^2 threads and a 256-thread workgroup holds 256 / NP^2 cells.
@@ -94,14 +73,11 @@ struct PoiLds {
 // every direction of its cell and reads the six neighbour pencils it needs
 // for the traces straight from global memory (no atomics: every output has
 // one writer).
+// The cells of block blk: [blk CB, (blk + 1) CB).
 template <typename T, int NP, int KIND>
-__global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y,
-                                                      int64_t ncell, int nblocks, int64_t vstride,
-                                                      const PoiEpi<T> E) {
+__device__ __forceinline__ void poisson_body(const MeshDev& M, const T* __restrict__ p, T* __restrict__ y,
+                                             int64_t ncell, int blk, const PoiEpi<T>& E) {
   using BL = PoiBlk<NP>;
-  // blockIdx.y selects one of several vectors stored vstride apart
-  p += blockIdx.y * vstride;
-  y += blockIdx.y * vstride;
   constexpr int NP2 = BL::NP2, NP3 = BL::NP3, CB = BL::CB;
   using LD = PoiLds<NP>;
   // In FP64 the input P and Q_x share one array (P is read into registers
@@ -112,11 +88,6 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   __shared__ T s_Y[CB * LD::SC];
   __shared__ T s_Z[CB * LD::SC];
   __shared__ T s_P[kAlias ? 1 : CB * LD::SC];
-
-  // contiguous cell ranges per XCD (workgroups are dealt round-robin over 8)
-  const int bid = blockIdx.x;
-  const int q8 = nblocks >> 3, r8 = nblocks & 7, xcd = bid & 7, m8 = bid >> 3;
-  const int blk = xcd * q8 + (xcd < r8 ? xcd : r8) + m8;
 
   const int tid = threadIdx.x;
   const int c = tid / NP2, t = tid - c * NP2;
@@ -349,6 +320,29 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   }
 }
 
+template <typename T, int NP, int KIND>
+__global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* __restrict__ p, T* __restrict__ y,
+                                                      int64_t ncell, int nblocks, int64_t vstride,
+                                                      const PoiEpi<T> E) {
+  // blockIdx.y selects one of several vectors stored vstride apart
+  p += blockIdx.y * vstride;
+  y += blockIdx.y * vstride;
+  // contiguous cell ranges per XCD (workgroups are dealt round-robin over 8)
+  const int bid = blockIdx.x;
+  const int q8 = nblocks >> 3, r8 = nblocks & 7, xcd = bid & 7, m8 = bid >> 3;
+  const int blk = xcd * q8 + (xcd < r8 ? xcd : r8) + m8;
+  poisson_body<T, NP, KIND>(M, p, y, ncell, blk, E);
+}
+
+// One launch over the segments of many meshes (cells of each segment in
+// order; small meshes, so no XCD remapping).
+template <typename T, int NP, int KIND>
+__global__ __launch_bounds__(256) void poisson_kernel_batched(const PoiSeg<T>* __restrict__ segs, int nseg) {
+  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
+  const PoiSeg<T>& S = segs[si];
+  poisson_body<T, NP, KIND>(S.M, S.p, S.y, S.ncell, (int)((int64_t)blockIdx.x - S.blk0), S.E);
+}
+
 // Diagonal of A for box cells.  The basis is a tensor product, so every term
 // separates into 1-D integrals: with M_i = int N_i^2, K_i = int N_i'^2 (Gauss
 // rule of the operator, exact), the cell term is
@@ -415,8 +409,12 @@ __global__ void poisson_diag_kernel(const MeshDev M, int64_t ncell, double* __re
   dg32[gid] = (float)acc;
 }
 
+}  // namespace
+
+#define DG_POI_COMBOS(X) X(2, 2) X(3, 3) X(4, 4) X(5, 5) X(6, 6)
+
 // Mesh arguments of multigrid level l (level 0: the mesh itself).
-MeshDev make_meshdev_p(const dg_mesh* m, int l = 0) {
+MeshDev poisson_meshdev(const dg_mesh* m, int l) {
   MeshDev M{};
   const MgLevel* lv = (l > 0) ? &m->mg[l] : nullptr;
   M.nx = lv ? lv->nx : m->P.nx;
@@ -438,9 +436,51 @@ MeshDev make_meshdev_p(const dg_mesh* m, int l = 0) {
   return M;
 }
 
+namespace {
+MeshDev make_meshdev_p(const dg_mesh* m, int l = 0) { return poisson_meshdev(m, l); }
 }  // namespace
 
-#define DG_POI_COMBOS(X) X(2, 2) X(3, 3) X(4, 4) X(5, 5) X(6, 6)
+int poisson_cells_per_block(int np) {
+  switch (np) {
+    case 2: return PoiBlk<2>::CB;
+    case 3: return PoiBlk<3>::CB;
+    case 4: return PoiBlk<4>::CB;
+    case 5: return PoiBlk<5>::CB;
+    case 6: return PoiBlk<6>::CB;
+  }
+  return 0;
+}
+
+template <typename T>
+int launch_poisson_batched(int np, int kind, const PoiSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
+  if (nseg <= 0 || nblk <= 0) return DG_OK;
+#define X(a, b)                                                                                                \
+  if (np == a) {                                                                                               \
+    switch (kind) {                                                                                            \
+      case kPlain:                                                                                             \
+        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kPlain>), dim3((unsigned)nblk), dim3(256), 0, s, segs,  \
+                           nseg);                                                                              \
+        break;                                                                                                 \
+      case kResid:                                                                                             \
+        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kResid>), dim3((unsigned)nblk), dim3(256), 0, s, segs,  \
+                           nseg);                                                                              \
+        break;                                                                                                 \
+      case kCheb:                                                                                              \
+        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kCheb>), dim3((unsigned)nblk), dim3(256), 0, s, segs,   \
+                           nseg);                                                                              \
+        break;                                                                                                 \
+      default:                                                                                                 \
+        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kChebFirst>), dim3((unsigned)nblk), dim3(256), 0, s,    \
+                           segs, nseg);                                                                        \
+    }                                                                                                          \
+    return check_hip(hipGetLastError(), "batched poisson kernel launch");                                      \
+  }
+  DG_POI_COMBOS(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "poisson degree not compiled");
+}
+template int launch_poisson_batched<double>(int, int, const PoiSeg<double>*, int, int64_t, hipStream_t);
+template int launch_poisson_batched<float>(int, int, const PoiSeg<float>*, int, int64_t, hipStream_t);
 
 bool poisson_supported(int np, int nq) {
 #define X(a, b) \

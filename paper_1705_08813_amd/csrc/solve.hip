@@ -19,12 +19,15 @@
 // The null space (constants) is handled by projecting b and x to zero mean.
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <cmath>
+#include <cstring>
+#include <type_traits>
 #include <vector>
 
-#include "dgwm_internal.h"
+#include "batch.h"
 
 namespace dgwm {
 
@@ -547,6 +550,38 @@ size_t solve_bytes_mesh(const dg_mesh& m) {
 
 namespace {
 
+// Work vectors of a solve on mesh m inside a workspace of solve_bytes(m)
+// bytes (the layout counted by solve_bytes_mesh).
+void carve_solver(Solver& S, const dg_mesh* m, void* ws, hipStream_t stream) {
+  S.m = m;
+  S.s = stream;
+  S.n = m->n_p;
+  S.grid = (unsigned)std::min<int64_t>((S.n + 255) / 256, 2048);
+  char* w = static_cast<char*>(ws);
+  auto take64 = [&](double*& p) { p = reinterpret_cast<double*>(w); w += up256(S.n * sizeof(double)); };
+  auto take32 = [&](float*& p) { p = reinterpret_cast<float*>(w); w += up256(S.n * sizeof(float)); };
+  take64(S.bp); take64(S.r); take64(S.z); take64(S.zold); take64(S.p); take64(S.q); take64(S.d64); take64(S.t64);
+  take64(S.dinv);
+  take32(S.r32); take32(S.z32); take32(S.d32); take32(S.t32); take32(S.x32); take32(S.rr32); take32(S.pp32);
+  take32(S.qq32); take32(S.dinv32);
+  S.sc = reinterpret_cast<double*>(w);
+  w += up256(64 * sizeof(double));
+  S.part = reinterpret_cast<double*>(w);
+  w += up256(2 * kRedBlocks * sizeof(double));
+  S.nlev = m->mg_nlev;
+  for (int l = 1; l < m->mg_nlev; ++l) {
+    const size_t bytes = up256((size_t)m->mg[l].n * sizeof(double));
+    Solver::Lv& v = S.lv[l];
+    v.n = m->mg[l].n;
+    v.x = w; w += bytes;
+    v.b = w; w += bytes;
+    v.r = w; w += bytes;
+    v.t = w; w += bytes;
+    v.dinv64 = reinterpret_cast<double*>(w); w += bytes;
+    v.dinv32 = reinterpret_cast<float*>(w); w += bytes;
+  }
+}
+
 // The solve on a workspace that holds at least solve_bytes(m) bytes; every
 // byte of it is written before it is read, so its previous contents do not
 // matter.  Allocates nothing (the pinned norm slot and its event belong to
@@ -561,34 +596,9 @@ int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* 
   if (b == x) return set_error(DG_ERR_ARG, "b and x must not alias");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Poisson operator is built for flat (box) meshes only");
   Solver S;
-  S.m = m;
-  S.s = static_cast<hipStream_t>(stream);
-  S.n = m->n_p;
-  S.grid = (unsigned)std::min<int64_t>((S.n + 255) / 256, 2048);
-  char* w = static_cast<char*>(ws);
-  auto take64 = [&](double*& p) { p = reinterpret_cast<double*>(w); w += up256(S.n * sizeof(double)); };
-  auto take32 = [&](float*& p) { p = reinterpret_cast<float*>(w); w += up256(S.n * sizeof(float)); };
-  take64(S.bp); take64(S.r); take64(S.z); take64(S.zold); take64(S.p); take64(S.q); take64(S.d64); take64(S.t64);
-  take64(S.dinv);
-  take32(S.r32); take32(S.z32); take32(S.d32); take32(S.t32); take32(S.x32); take32(S.rr32); take32(S.pp32);
-  take32(S.qq32); take32(S.dinv32);
-  S.sc = reinterpret_cast<double*>(w);
-  w += up256(64 * sizeof(double));
-  S.part = reinterpret_cast<double*>(w);
-  w += up256(2 * kRedBlocks * sizeof(double));
+  carve_solver(S, m, ws, static_cast<hipStream_t>(stream));
   const bool use_mg = sp->multigrid && m->mg_nlev > 1;
   S.nlev = use_mg ? m->mg_nlev : 0;
-  for (int l = 1; l < m->mg_nlev; ++l) {
-    const size_t bytes = up256((size_t)m->mg[l].n * sizeof(double));
-    Solver::Lv& v = S.lv[l];
-    v.n = m->mg[l].n;
-    v.x = w; w += bytes;
-    v.b = w; w += bytes;
-    v.r = w; w += bytes;
-    v.t = w; w += bytes;
-    v.dinv64 = reinterpret_cast<double*>(w); w += bytes;
-    v.dinv32 = reinterpret_cast<float*>(w); w += bytes;
-  }
   double* sc = S.sc;
   enum { RZ0 = 0, RZ1 = 1, PQ = 2, RR = 3, RZX = 4, SUM = 5, NB = 6, SCL = 7, IRZ0 = 8, IRZ1 = 9, IPQ = 10, IRR = 11 };
   int rc;
@@ -763,6 +773,1046 @@ int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Batched solves (the serving path): the solves of many meshes advance in
+// lockstep, one outer iteration at a time, and every step of an iteration
+// (operator applications, smoothing, transfers, vector updates, reductions)
+// is one launch over all meshes of the batch (per degree group), driven by
+// descriptor tables (batch.h) that stay in device memory while the set of
+// unconverged meshes is unchanged.  Each mesh runs the same arithmetic as
+// it would in a batch of one: its results do not depend on the others.
+// ---------------------------------------------------------------------------
+namespace {
+
+// One mesh's part of a batched vector operation.
+struct VSeg {
+  int64_t blk0;
+  int64_t n;     // entries (V_FINAL: partials to add; V_GATHER: output row)
+  int64_t nblk;  // workgroups of this segment
+  const void* a;
+  const void* b;
+  const void* c;
+  void* d;
+  void* e;
+  double* sc;    // the mesh's device scalars
+  double* part;  // the mesh's reduction partials
+  double coef;
+};
+
+enum VOp {
+  V_SUM, V_SUB_MEAN, V_COPY_SUB_MEAN, V_DOT, V_DOT2, V_FINAL, V_GATHER, V_UPDATE_XR, V_UPDATE_P, V_RESID, V_TO_F32,
+  V_FROM_F32_DOT2, V_FILL, V_COPY, V_RECIP64, V_RECIP32, V_HASH, V_JACOBI, V_CHEB_FIRST64, V_CHEB_FIRST32
+};
+
+constexpr bool vop_reduces(int op) {
+  return op == V_SUM || op == V_DOT || op == V_DOT2 || op == V_UPDATE_XR || op == V_FROM_F32_DOT2;
+}
+
+// Workgroups per mesh: reductions use a block count that depends on the
+// vector length only (deterministic partials), one block for the finals.
+int64_t vop_blocks(int op, int64_t n) {
+  if (op == V_FINAL || op == V_GATHER) return 1;
+  if (vop_reduces(op)) return std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 256));
+  return std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 1024));
+}
+
+// i0..i3: scalar slots of the operation (see the cases).
+template <int OP>
+__global__ __launch_bounds__(kRedThreads) void k_vop(const VSeg* __restrict__ segs, int nseg, int i0, int i1, int i2,
+                                                     int i3, double* __restrict__ gather) {
+  __shared__ double sh[kRedThreads / 64];
+  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
+  const VSeg S = segs[si];
+  const int64_t lb = (int64_t)blockIdx.x - S.blk0;
+  const int64_t n = S.n, st = S.nblk * (int64_t)blockDim.x;
+  const int64_t i00 = lb * (int64_t)blockDim.x + threadIdx.x;
+  double* sc = S.sc;
+  if constexpr (OP == V_SUM) {  // part = sum a
+    const double* a = static_cast<const double*>(S.a);
+    double v = 0;
+    for (int64_t i = i00; i < n; i += st) v += a[i];
+    v = block_reduce(v, sh);
+    if (threadIdx.x == 0) S.part[lb] = v;
+  } else if constexpr (OP == V_SUB_MEAN) {  // d -= sc[i0] / n
+    double* d = static_cast<double*>(S.d);
+    const double mean = sc[i0] / (double)n;
+    for (int64_t i = i00; i < n; i += st) d[i] -= mean;
+  } else if constexpr (OP == V_COPY_SUB_MEAN) {  // d = a - sc[i0] / n
+    double* d = static_cast<double*>(S.d);
+    const double* a = static_cast<const double*>(S.a);
+    const double mean = sc[i0] / (double)n;
+    for (int64_t i = i00; i < n; i += st) d[i] = a[i] - mean;
+  } else if constexpr (OP == V_DOT) {  // part = a.b
+    const double* a = static_cast<const double*>(S.a);
+    const double* b = static_cast<const double*>(S.b);
+    double v = 0;
+    for (int64_t i = i00; i < n; i += st) v += a[i] * b[i];
+    v = block_reduce(v, sh);
+    if (threadIdx.x == 0) S.part[lb] = v;
+  } else if constexpr (OP == V_DOT2) {  // part = a.b, part + nblk = a.c
+    const double* a = static_cast<const double*>(S.a);
+    const double* b = static_cast<const double*>(S.b);
+    const double* c = static_cast<const double*>(S.c);
+    double v1 = 0, v2 = 0;
+    for (int64_t i = i00; i < n; i += st) {
+      v1 += a[i] * b[i];
+      v2 += a[i] * c[i];
+    }
+    v1 = block_reduce(v1, sh);
+    __syncthreads();
+    v2 = block_reduce(v2, sh);
+    if (threadIdx.x == 0) {
+      S.part[lb] = v1;
+      S.part[S.nblk + lb] = v2;
+    }
+  } else if constexpr (OP == V_FINAL) {  // sc[i0] = sum of n partials (sc[i1]: the next n, if i1 >= 0)
+    double v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += S.part[i];
+    v = block_reduce(v, sh);
+    if (threadIdx.x == 0) sc[i0] = v;
+    if (i1 >= 0) {
+      __syncthreads();
+      v = 0;
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += S.part[n + i];
+      v = block_reduce(v, sh);
+      if (threadIdx.x == 0) sc[i1] = v;
+    }
+  } else if constexpr (OP == V_GATHER) {  // gather[n i2 + j] = sc[i0 + j], j < i1
+    for (int j = threadIdx.x; j < i1; j += blockDim.x) gather[n * i2 + j] = sc[i0 + j];
+  } else if constexpr (OP == V_UPDATE_XR) {
+    // x (d) += alpha p (a), r (e) -= alpha q (b), alpha = sc[i0] / sc[i1]; with c != nullptr the new
+    // residual also goes to c in FP32 divided by sqrt(sc[i2]), that divisor stored in sc[i3]; part = r.r
+    double* x = static_cast<double*>(S.d);
+    double* r = static_cast<double*>(S.e);
+    const double* p = static_cast<const double*>(S.a);
+    const double* q = static_cast<const double*>(S.b);
+    float* r32 = static_cast<float*>(const_cast<void*>(S.c));
+    const double alpha = sc[i0] / sc[i1];
+    const double nrm = r32 ? sqrt(sc[i2]) : 1.0, inv = 1.0 / nrm;
+    double v = 0;
+    for (int64_t i = i00; i < n; i += st) {
+      x[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      if (r32) r32[i] = (float)(ri * inv);
+      v += ri * ri;
+    }
+    v = block_reduce(v, sh);
+    if (threadIdx.x == 0) S.part[lb] = v;
+    if (r32 && lb == 0 && threadIdx.x == 0) sc[i3] = nrm;
+  } else if constexpr (OP == V_UPDATE_P) {  // p (d) = z (a) + beta p, beta = (sc[i0] - sc[i1]) / sc[i2]
+    double* p = static_cast<double*>(S.d);
+    const double* z = static_cast<const double*>(S.a);
+    const double beta = (sc[i0] - (i1 >= 0 ? sc[i1] : 0.0)) / sc[i2];
+    for (int64_t i = i00; i < n; i += st) p[i] = z[i] + beta * p[i];
+  } else if constexpr (OP == V_RESID) {  // d = a - b
+    double* d = static_cast<double*>(S.d);
+    const double* a = static_cast<const double*>(S.a);
+    const double* b = static_cast<const double*>(S.b);
+    for (int64_t i = i00; i < n; i += st) d[i] = a[i] - b[i];
+  } else if constexpr (OP == V_TO_F32) {  // d = a / sqrt(sc[i0]) in FP32, the divisor stored in sc[i1]
+    float* d = static_cast<float*>(S.d);
+    const double* a = static_cast<const double*>(S.a);
+    const double nrm = sqrt(sc[i0]), inv = 1.0 / nrm;
+    for (int64_t i = i00; i < n; i += st) d[i] = (float)(a[i] * inv);
+    if (lb == 0 && threadIdx.x == 0) sc[i1] = nrm;
+  } else if constexpr (OP == V_FROM_F32_DOT2) {
+    // z (d) = sc[i0] x32 (a); part = r (b) . z, part + nblk = r . zold (c, if not null)
+    double* z = static_cast<double*>(S.d);
+    const float* x = static_cast<const float*>(S.a);
+    const double* r = static_cast<const double*>(S.b);
+    const double* zo = static_cast<const double*>(S.c);
+    const double s = sc[i0];
+    double v1 = 0, v2 = 0;
+    for (int64_t i = i00; i < n; i += st) {
+      const double zi = s * (double)x[i], ri = r[i];
+      z[i] = zi;
+      v1 += ri * zi;
+      if (zo) v2 += ri * zo[i];
+    }
+    v1 = block_reduce(v1, sh);
+    __syncthreads();
+    v2 = block_reduce(v2, sh);
+    if (threadIdx.x == 0) {
+      S.part[lb] = v1;
+      S.part[S.nblk + lb] = v2;
+    }
+  } else if constexpr (OP == V_FILL) {
+    double* d = static_cast<double*>(S.d);
+    for (int64_t i = i00; i < n; i += st) d[i] = 0.0;
+  } else if constexpr (OP == V_COPY) {
+    double* d = static_cast<double*>(S.d);
+    const double* a = static_cast<const double*>(S.a);
+    for (int64_t i = i00; i < n; i += st) d[i] = a[i];
+  } else if constexpr (OP == V_RECIP64) {
+    double* d = static_cast<double*>(S.d);
+    const double* a = static_cast<const double*>(S.a);
+    for (int64_t i = i00; i < n; i += st) d[i] = 1.0 / a[i];
+  } else if constexpr (OP == V_RECIP32) {
+    float* d = static_cast<float*>(S.d);
+    const double* a = static_cast<const double*>(S.a);
+    for (int64_t i = i00; i < n; i += st) d[i] = (float)(1.0 / a[i]);
+  } else if constexpr (OP == V_HASH) {  // the start vector of the single-mesh Lanczos
+    double* d = static_cast<double*>(S.d);
+    for (int64_t i = i00; i < n; i += st) {
+      uint64_t z = (uint64_t)i + 0x9E3779B97F4A7C15ull;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z ^= z >> 31;
+      d[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+  } else if constexpr (OP == V_JACOBI) {  // d = e = dinv (b) r (a)
+    double* d = static_cast<double*>(S.d);
+    double* e = static_cast<double*>(S.e);
+    const double* r = static_cast<const double*>(S.a);
+    const double* di = static_cast<const double*>(S.b);
+    for (int64_t i = i00; i < n; i += st) {
+      const double v = di[i] * r[i];
+      d[i] = v;
+      e[i] = v;
+    }
+  } else if constexpr (OP == V_CHEB_FIRST64 || OP == V_CHEB_FIRST32) {  // d = e = coef dinv (b) r (a)
+    using T = typename std::conditional<OP == V_CHEB_FIRST64, double, float>::type;
+    T* d = static_cast<T*>(S.d);
+    T* e = static_cast<T*>(S.e);
+    const T* r = static_cast<const T*>(S.a);
+    const T* di = static_cast<const T*>(S.b);
+    const T c = (T)S.coef;
+    for (int64_t i = i00; i < n; i += st) {
+      const T v = c * di[i] * r[i];
+      d[i] = v;
+      e[i] = v;
+    }
+  }
+}
+
+// Scalar slots of a mesh's sc[] (as in the single solve; 16 and 20..59: Lanczos)
+enum { B_RZ0 = 0, B_RZ1 = 1, B_PQ = 2, B_RR = 3, B_RZX = 4, B_SUM = 5, B_NB = 6, B_SCL = 7, B_LSUM = 16, B_LRZ = 20,
+       B_LPQ = 40 };
+constexpr int kLanczosSteps = 20;
+constexpr int kGatherRow = 2 * kLanczosSteps;  // doubles per mesh in the gather array
+
+struct BInst {
+  const dg_mesh* m = nullptr;
+  Solver S;
+  const double* b = nullptr;
+  double* x = nullptr;
+  int idx = 0;             // position in the caller's arrays (row of the gather array)
+  double nb = 0, rn = 0;
+  int it = 0;
+  int code = DG_OK;
+  bool done = false;
+  int applies64 = 0, applies32 = 0;
+  double seconds = 0;
+};
+
+// Descriptor bytes and the launches that use them.
+struct Prog {
+  std::vector<char> tab;
+  std::vector<std::function<int(const char*, hipStream_t)>> steps;
+  std::vector<BInst*> who;   // meshes whose applies are counted
+  std::vector<int> a64, a32;  // level-0 operator applications per run, per entry of who
+  const char* dev = nullptr;
+  int epoch = -1;
+  int64_t put_bytes(const void* p, size_t bytes) {
+    const size_t off = (tab.size() + 255) & ~size_t(255);
+    tab.resize(off + bytes);
+    std::memcpy(tab.data() + off, p, bytes);
+    return (int64_t)off;
+  }
+  void count(BInst* in, bool f64) {
+    for (size_t k = 0; k < who.size(); ++k)
+      if (who[k] == in) {
+        (f64 ? a64 : a32)[k]++;
+        return;
+      }
+    who.push_back(in);
+    a64.push_back(f64 ? 1 : 0);
+    a32.push_back(f64 ? 0 : 1);
+  }
+};
+
+using Set = std::vector<BInst*>;
+
+// Host staging for the descriptor uploads and the scalar read-backs: pinned
+// memory per host thread, kept for the thread's lifetime and grown on demand.
+struct Pinned {
+  char* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+};
+thread_local Pinned tl_pinned;
+
+int pinned_get(size_t bytes, char** out, hipEvent_t* ev) {
+  Pinned& P = tl_pinned;
+  if (!P.ev && hipEventCreateWithFlags(&P.ev, hipEventDisableTiming) != hipSuccess)
+    return set_error(DG_ERR_HIP, "event creation failed");
+  if (P.cap < bytes) {
+    if (P.p) (void)hipHostFree(P.p);
+    P.p = nullptr;
+    P.cap = 0;
+    void* q = nullptr;
+    if (int rc = check_hip(hipHostMalloc(&q, bytes, hipHostMallocDefault), "pinned staging")) return rc;
+    P.p = static_cast<char*>(q);
+    P.cap = bytes;
+  }
+  *out = P.p;
+  *ev = P.ev;
+  return DG_OK;
+}
+
+class Batch {
+ public:
+  std::vector<BInst> I;
+  const dg_solve_params* sp = nullptr;
+  hipStream_t s = nullptr;
+  double* gather = nullptr;   // device: kGatherRow doubles per mesh
+  char* arena = nullptr;      // device descriptor arena
+  size_t arena_cap = 0, top = 0;
+  int epoch = 0;
+  char* stage = nullptr;      // pinned: same offsets as the arena, then the read-back rows
+  double* rb = nullptr;
+  hipEvent_t ev = nullptr;
+  bool mixed = false;
+  int deg0 = 1, degc = 1;
+
+  // ---- upload and run ----
+  int upload(Prog& P) {
+    if (P.epoch == epoch) return DG_OK;
+    const size_t need = (P.tab.size() + 255) & ~size_t(255);
+    if (need > arena_cap) return set_error(DG_ERR_WORKSPACE, "batched solve: descriptor workspace too small");
+    if (top + need > arena_cap) {
+      // every launch that reads the arena (and every copy from the staging
+      // area) has run once the stream is idle
+      if (int rc = check_hip(hipStreamSynchronize(s), "descriptor arena reuse")) return rc;
+      top = 0;
+      ++epoch;
+    }
+    std::memcpy(stage + top, P.tab.data(), P.tab.size());
+    if (int rc = check_hip(hipMemcpyAsync(arena + top, stage + top, P.tab.size(), hipMemcpyHostToDevice, s),
+                           "descriptor upload"))
+      return rc;
+    P.dev = arena + top;
+    P.epoch = epoch;
+    top += need;
+    return DG_OK;
+  }
+  int run(Prog& P) {
+    if (P.steps.empty()) return DG_OK;
+    if (int rc = upload(P)) return rc;
+    for (auto& f : P.steps)
+      if (int rc = f(P.dev, s)) return rc;
+    for (size_t k = 0; k < P.who.size(); ++k) {
+      P.who[k]->applies64 += P.a64[k];
+      P.who[k]->applies32 += P.a32[k];
+    }
+    return DG_OK;
+  }
+  // copy `rows` gather rows of the set's meshes to the host (asynchronous; wait())
+  int readback() {
+    if (int rc = check_hip(hipMemcpyAsync(rb, gather, sizeof(double) * kGatherRow * I.size(), hipMemcpyDeviceToHost,
+                                          s), "scalar read-back"))
+      return rc;
+    return check_hip(hipEventRecord(ev, s), "read-back event");
+  }
+  int wait() { return check_hip(hipEventSynchronize(ev), "read-back wait"); }
+
+  // ---- builders ----
+  template <int OP>
+  void vop(Prog& P, const Set& set, const std::function<void(VSeg&, BInst&)>& fill, int i0 = -1, int i1 = -1,
+           int i2 = -1, int i3 = -1) {
+    std::vector<VSeg> v;
+    int64_t blk = 0;
+    for (BInst* in : set) {
+      VSeg g{};
+      g.sc = in->S.sc;
+      g.part = in->S.part;
+      fill(g, *in);
+      g.blk0 = blk;
+      g.nblk = vop_blocks(OP, g.n);
+      blk += g.nblk;
+      v.push_back(g);
+    }
+    if (v.empty()) return;
+    const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(VSeg));
+    const int nseg = (int)v.size();
+    double* ga = gather;
+    P.steps.push_back([=](const char* base, hipStream_t st) {
+      hipLaunchKernelGGL((k_vop<OP>), dim3((unsigned)blk), dim3(kRedThreads), 0, st,
+                         reinterpret_cast<const VSeg*>(base + off), nseg, i0, i1, i2, i3, ga);
+      return check_hip(hipGetLastError(), "batched vector launch");
+    });
+  }
+  // sc[o1] (and sc[o2]) = the reduction just built into the partials (n entries each)
+  template <int OP>
+  void reduce(Prog& P, const Set& set, const std::function<void(VSeg&, BInst&)>& fill, int o1, int o2 = -1) {
+    vop<OP>(P, set, fill);
+    vop<V_FINAL>(P, set, [&](VSeg& g, BInst& in) {
+      VSeg t{};
+      fill(t, in);
+      g.n = vop_blocks(OP, t.n);
+    }, o1, o2);
+  }
+  void gather_rows(Prog& P, const Set& set, int slot, int count) {
+    vop<V_GATHER>(P, set, [](VSeg& g, BInst& in) { g.n = in.idx; }, slot, count, kGatherRow);
+  }
+
+  template <typename T>
+  void poi(Prog& P, int kind, const Set& set, int l, const std::function<void(PoiSeg<T>&, BInst&)>& fill) {
+    // one launch per degree group
+    std::vector<int> nps;
+    for (BInst* in : set)
+      if (std::find(nps.begin(), nps.end(), in->m->np_p) == nps.end()) nps.push_back(in->m->np_p);
+    for (int np : nps) {
+      std::vector<PoiSeg<T>> v;
+      int64_t blk = 0;
+      const int cb = poisson_cells_per_block(np);
+      for (BInst* in : set) {
+        if (in->m->np_p != np) continue;
+        PoiSeg<T> g{};
+        g.M = poisson_meshdev(in->m, l);
+        g.ncell = l > 0 ? in->m->mg[l].ncell : in->m->ncell;
+        fill(g, *in);
+        g.E.kind = kind;
+        g.blk0 = blk;
+        blk += (g.ncell + cb - 1) / cb;
+        v.push_back(g);
+        if (l == 0) P.count(in, sizeof(T) == 8);
+      }
+      const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(PoiSeg<T>));
+      const int nseg = (int)v.size();
+      P.steps.push_back([=](const char* base, hipStream_t st) {
+        return launch_poisson_batched<T>(np, kind, reinterpret_cast<const PoiSeg<T>*>(base + off), nseg, blk, st);
+      });
+    }
+  }
+  template <typename T>
+  void xfer(Prog& P, bool restrict_, const Set& set, int l, const std::function<void(TrSeg<T>&, BInst&)>& fill) {
+    std::vector<std::pair<int, bool>> groups;
+    for (BInst* in : set) {
+      const std::pair<int, bool> g(in->m->np_p, mg_full_transfer(in->m, l));
+      if (std::find(groups.begin(), groups.end(), g) == groups.end()) groups.push_back(g);
+    }
+    for (const auto& gr : groups) {
+      std::vector<TrSeg<T>> v;
+      int64_t blk = 0;
+      const int cpc = mg_cells_per_block(gr.first, gr.second);
+      for (BInst* in : set) {
+        if (in->m->np_p != gr.first || mg_full_transfer(in->m, l) != gr.second) continue;
+        TrSeg<T> g{};
+        g.tr = mg_transfer_geometry(in->m, l);
+        g.ncc = in->m->mg[l + 1].ncell;
+        fill(g, *in);
+        g.blk0 = blk;
+        blk += (g.ncc + cpc - 1) / cpc;
+        v.push_back(g);
+      }
+      const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(TrSeg<T>));
+      const int nseg = (int)v.size();
+      const int np = gr.first;
+      const bool full = gr.second;
+      P.steps.push_back([=](const char* base, hipStream_t st) {
+        const TrSeg<T>* d = reinterpret_cast<const TrSeg<T>*>(base + off);
+        return restrict_ ? launch_mg_restrict_batched<T>(np, full, d, nseg, blk, st)
+                         : launch_mg_prolong_batched<T>(np, full, d, nseg, blk, st);
+      });
+    }
+  }
+  template <typename T>
+  void dense(Prog& P, const Set& set, int l, const std::function<void(DenseSeg<T>&, BInst&)>& fill) {
+    std::vector<DenseSeg<T>> v;
+    int64_t blk = 0;
+    const int rpb = dense_rows_per_block();
+    for (BInst* in : set) {
+      DenseSeg<T> g{};
+      g.n = in->m->mg[l].n;
+      g.B = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)in->m->coarse_inv
+                                                      : (const void*)in->m->coarse_inv32);
+      fill(g, *in);
+      g.blk0 = blk;
+      blk += (g.n + rpb - 1) / rpb;
+      v.push_back(g);
+    }
+    if (v.empty()) return;
+    const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(DenseSeg<T>));
+    const int nseg = (int)v.size();
+    P.steps.push_back([=](const char* base, hipStream_t st) {
+      return launch_dense_batched<T>(reinterpret_cast<const DenseSeg<T>*>(base + off), nseg, blk, st);
+    });
+  }
+
+  // ---- multigrid V-cycle in lockstep ----
+  // level buffers of mesh `in` at level l (l = 0: the caller's four)
+  enum Buf { BX = 0, BB = 1, BR = 2, BT = 3 };
+  template <typename T>
+  struct L0 {
+    std::function<T*(BInst&)> b[4];
+  };
+  template <typename T>
+  static T* lvbuf(BInst& in, int l, int which) {
+    Solver::Lv& v = in.S.lv[l];
+    char* p = which == BX ? v.x : (which == BB ? v.b : (which == BR ? v.r : v.t));
+    return reinterpret_cast<T*>(p);
+  }
+  template <typename T>
+  static const T* dinv_l(BInst& in, int l) {
+    if (sizeof(T) == 8) return reinterpret_cast<const T*>(l == 0 ? in.S.dinv : in.S.lv[l].dinv64);
+    return reinterpret_cast<const T*>(l == 0 ? in.S.dinv32 : in.S.lv[l].dinv32);
+  }
+  static int64_t n_l(const BInst& in, int l) { return l == 0 ? in.m->n_p : in.m->mg[l].n; }
+
+  // z = Cheb_deg(D^-1 A_l) D^-1 b from a zero start, per mesh interval [lam/lo, hi lam] (Solver::cheb_l)
+  template <typename T>
+  void cheb_l(Prog& P, const Set& set, int l, const std::function<T*(BInst&, int)>& buf, int deg, double lo_div,
+              double hi_mul) {
+    // per mesh coefficients
+    struct Co { double theta, delta, sigma; };
+    auto co = [&](BInst& in) {
+      const double lam = in.m->mg[l].lam, lmin = lam / lo_div, lmax = hi_mul * lam;
+      Co c;
+      c.theta = 0.5 * (lmax + lmin);
+      c.delta = 0.5 * (lmax - lmin);
+      c.sigma = c.theta / c.delta;
+      return c;
+    };
+    const bool cur_t = ((deg - 1) % 2) != 0;  // the first iterate lands in t for an even step count
+    if (deg == 1) {
+      vop<sizeof(T) == 8 ? V_CHEB_FIRST64 : V_CHEB_FIRST32>(P, set, [&](VSeg& g, BInst& in) {
+        g.n = n_l(in, l);
+        g.d = buf(in, cur_t ? BT : BX);
+        g.e = buf(in, cur_t ? BX : BT);
+        g.a = buf(in, BB);
+        g.b = dinv_l<T>(in, l);
+        g.coef = 1.0 / co(in).theta;
+      });
+      return;
+    }
+    bool cur_is_t = cur_t;
+    for (int k = 1; k < deg; ++k) {
+      const int cur = cur_is_t ? BT : BX, oth = cur_is_t ? BX : BT;
+      const int kk = k;
+      poi<T>(P, k == 1 ? kChebFirst : kCheb, set, l, [&](PoiSeg<T>& g, BInst& in) {
+        const Co c = co(in);
+        double rho = 1.0 / c.sigma, rho_new = 0;
+        for (int j = 1; j <= kk; ++j) {
+          rho_new = 1.0 / (2.0 * c.sigma - rho);
+          if (j < kk) rho = rho_new;
+        }
+        g.E.b = buf(in, BB);
+        g.E.dinv = dinv_l<T>(in, l);
+        g.E.c1 = (T)(rho_new * rho);
+        g.E.c2 = (T)(2.0 * rho_new / c.delta);
+        if (kk == 1) {
+          g.p = buf(in, BB);
+          g.E.z1 = buf(in, cur);
+          g.E.zout = buf(in, oth);
+          g.E.c0 = (T)(1.0 / c.theta);
+        } else {
+          g.p = buf(in, cur);
+          g.E.zout = buf(in, oth);
+        }
+      });
+      cur_is_t = !cur_is_t;
+    }
+  }
+  // the same polynomial continued from the current iterate (Solver::cheb_from)
+  template <typename T>
+  void cheb_from(Prog& P, const Set& set, int l, const std::function<T*(BInst&, int)>& buf, int deg) {
+    bool cur_is_t = (deg % 2) != 0;
+    for (int k = 0; k < deg; ++k) {
+      const int cur = cur_is_t ? BT : BX, oth = cur_is_t ? BX : BT;
+      const int kk = k;
+      poi<T>(P, kCheb, set, l, [&](PoiSeg<T>& g, BInst& in) {
+        const double lam = in.m->mg[l].lam, lmin = lam / kSmoothRange, lmax = 1.1 * lam;
+        const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+        double c1 = 0, c2 = 1.0 / theta, rho = 1.0 / sigma;
+        for (int j = 1; j <= kk; ++j) {
+          const double rho_new = 1.0 / (2.0 * sigma - rho);
+          c1 = rho_new * rho;
+          c2 = 2.0 * rho_new / delta;
+          rho = rho_new;
+        }
+        g.p = buf(in, cur);
+        g.E.b = buf(in, BB);
+        g.E.dinv = dinv_l<T>(in, l);
+        g.E.zout = buf(in, oth);
+        g.E.c1 = (T)c1;
+        g.E.c2 = (T)c2;
+      });
+      cur_is_t = !cur_is_t;
+    }
+  }
+  template <typename T>
+  void vcycle(Prog& P, const Set& set, int l, const std::function<T*(BInst&, int)>& buf) {
+    if (set.empty()) return;
+    const int deg = l == 0 ? deg0 : degc;
+    Set coarse_d, coarse_c, mid;
+    for (BInst* in : set) {
+      if (l == in->S.nlev - 1) (in->m->coarse_inv ? coarse_d : coarse_c).push_back(in);
+      else mid.push_back(in);
+    }
+    dense<T>(P, coarse_d, l, [&](DenseSeg<T>& g, BInst& in) {
+      g.b = buf(in, BB);
+      g.x = buf(in, BX);
+    });
+    if (!coarse_c.empty()) cheb_l<T>(P, coarse_c, l, buf, 4 * deg0, 200.0, 1.1);
+    if (mid.empty()) return;
+    cheb_l<T>(P, mid, l, buf, deg, kSmoothRange, 1.1);
+    poi<T>(P, kResid, mid, l, [&](PoiSeg<T>& g, BInst& in) {
+      g.p = buf(in, BX);
+      g.y = buf(in, BR);
+      g.E.b = buf(in, BB);
+    });
+    xfer<T>(P, true, mid, l, [&](TrSeg<T>& g, BInst& in) {
+      g.in = buf(in, BR);
+      g.out = lvbuf<T>(in, l + 1, BB);
+    });
+    const int lc = l + 1;
+    vcycle<T>(P, mid, lc, [lc](BInst& in, int w) { return lvbuf<T>(in, lc, w); });
+    xfer<T>(P, false, mid, l, [&](TrSeg<T>& g, BInst& in) {
+      g.in = lvbuf<T>(in, lc, BX);
+      g.add = buf(in, BX);
+      g.out = buf(in, (deg % 2) ? BT : BX);
+    });
+    cheb_from<T>(P, mid, l, buf, deg);
+  }
+
+  // z = M^{-1} r, then r.z -> sc[rz] and (zold) r.zold -> sc[rzx] (precond_dots of the single solve)
+  void precond_dots(Prog& P, const Set& set, int zsel, bool r32_ready, int zoldsel, int rz, int rzx) {
+    auto zb = [zsel](BInst& in) { return zsel == 0 ? in.S.z : in.S.zold; };
+    auto zo = [zoldsel](BInst& in) -> double* { return zoldsel < 0 ? nullptr : (zoldsel == 0 ? in.S.z : in.S.zold); };
+    if (mixed) {
+      if (!r32_ready)
+        vop<V_TO_F32>(P, set, [](VSeg& g, BInst& in) {
+          g.n = in.m->n_p;
+          g.d = in.S.r32;
+          g.a = in.S.r;
+        }, B_RR, B_SCL);
+      vcycle<float>(P, set, 0, [](BInst& in, int w) {
+        return w == BX ? in.S.x32 : (w == BB ? in.S.r32 : (w == BR ? in.S.rr32 : in.S.t32));
+      });
+      reduce<V_FROM_F32_DOT2>(P, set, [&](VSeg& g, BInst& in) {
+        g.n = in.m->n_p;
+        g.d = zb(in);
+        g.a = in.S.x32;
+        g.b = in.S.r;
+        g.c = zo(in);
+      }, rz, zoldsel >= 0 ? rzx : -1);
+      return;
+    }
+    vcycle<double>(P, set, 0, [zb](BInst& in, int w) {
+      return w == BX ? zb(in) : (w == BB ? in.S.r : (w == BR ? in.S.q : in.S.t64));
+    });
+    if (zoldsel >= 0)
+      reduce<V_DOT2>(P, set, [&](VSeg& g, BInst& in) {
+        g.n = in.m->n_p;
+        g.a = in.S.r;
+        g.b = zb(in);
+        g.c = zo(in);
+      }, rz, rzx);
+    else
+      reduce<V_DOT>(P, set, [&](VSeg& g, BInst& in) {
+        g.n = in.m->n_p;
+        g.a = in.S.r;
+        g.b = zb(in);
+      }, rz);
+  }
+  // r = b' - A x, r.r -> sc[RR], gathered
+  void true_residual(Prog& P, const Set& set) {
+    poi<double>(P, kPlain, set, 0, [](PoiSeg<double>& g, BInst& in) {
+      g.p = in.x;
+      g.y = in.S.q;
+    });
+    vop<V_RESID>(P, set, [](VSeg& g, BInst& in) {
+      g.n = in.m->n_p;
+      g.d = in.S.r;
+      g.a = in.S.bp;
+      g.b = in.S.q;
+    });
+    reduce<V_DOT>(P, set, [](VSeg& g, BInst& in) {
+      g.n = in.m->n_p;
+      g.a = in.S.r;
+      g.b = in.S.r;
+    }, B_RR);
+    gather_rows(P, set, B_RR, 1);
+  }
+  void project_x(Prog& P, const Set& set) {
+    reduce<V_SUM>(P, set, [](VSeg& g, BInst& in) {
+      g.n = in.m->n_p;
+      g.a = in.x;
+    }, B_SUM);
+    vop<V_SUB_MEAN>(P, set, [](VSeg& g, BInst& in) {
+      g.n = in.m->n_p;
+      g.d = in.x;
+    }, B_SUM);
+  }
+  // 20 Jacobi-PCG steps on level l of every mesh of the set (Solver::lanczos)
+  void lanczos(Prog& P, const Set& set, int l) {
+    vop<V_HASH>(P, set, [l](VSeg& g, BInst& in) {
+      g.n = n_l(in, l);
+      g.d = in.S.r;
+    });
+    reduce<V_SUM>(P, set, [l](VSeg& g, BInst& in) {
+      g.n = n_l(in, l);
+      g.a = in.S.r;
+    }, B_LSUM);
+    vop<V_SUB_MEAN>(P, set, [l](VSeg& g, BInst& in) {
+      g.n = n_l(in, l);
+      g.d = in.S.r;
+    }, B_LSUM);
+    vop<V_FILL>(P, set, [l](VSeg& g, BInst& in) {
+      g.n = n_l(in, l);
+      g.d = in.S.t64;
+    });
+    for (int k = 0; k < kLanczosSteps; ++k) {
+      vop<V_JACOBI>(P, set, [l](VSeg& g, BInst& in) {
+        g.n = n_l(in, l);
+        g.d = in.S.z;
+        g.e = in.S.d64;
+        g.a = in.S.r;
+        g.b = dinv_l<double>(in, l);
+      });
+      reduce<V_DOT>(P, set, [l](VSeg& g, BInst& in) {
+        g.n = n_l(in, l);
+        g.a = in.S.r;
+        g.b = in.S.z;
+      }, B_LRZ + k);
+      if (k == 0)
+        vop<V_COPY>(P, set, [l](VSeg& g, BInst& in) {
+          g.n = n_l(in, l);
+          g.d = in.S.p;
+          g.a = in.S.z;
+        });
+      else
+        vop<V_UPDATE_P>(P, set, [l](VSeg& g, BInst& in) {
+          g.n = n_l(in, l);
+          g.d = in.S.p;
+          g.a = in.S.z;
+        }, B_LRZ + k, -1, B_LRZ + k - 1);
+      poi<double>(P, kPlain, set, l, [](PoiSeg<double>& g, BInst& in) {
+        g.p = in.S.p;
+        g.y = in.S.q;
+      });
+      reduce<V_DOT>(P, set, [l](VSeg& g, BInst& in) {
+        g.n = n_l(in, l);
+        g.a = in.S.p;
+        g.b = in.S.q;
+      }, B_LPQ + k);
+      vop<V_UPDATE_XR>(P, set, [l](VSeg& g, BInst& in) {
+        g.n = n_l(in, l);
+        g.d = in.S.t64;
+        g.e = in.S.r;
+        g.a = in.S.p;
+        g.b = in.S.q;
+      }, B_LRZ + k, B_LPQ + k);
+    }
+    gather_rows(P, set, B_LRZ, 2 * kLanczosSteps);
+  }
+};
+
+// lmax from the Lanczos coefficients of one mesh level (as Solver::lanczos)
+int lanczos_lmax(const double* h, double* out) {
+  constexpr int K = kLanczosSteps;
+  double al[K], be[K], diag[K], off[K];
+  int kk = 0;
+  for (int k = 0; k < K; ++k) {
+    const double rz = h[k], pq = h[K + k];
+    if (!(rz > 0) || !(pq > 0) || !std::isfinite(rz) || !std::isfinite(pq)) break;
+    if (k > 0) be[k - 1] = rz / h[k - 1];
+    al[k] = rz / pq;
+    kk = k + 1;
+  }
+  if (kk < 1) return set_error(DG_ERR_NONFINITE, "eigenvalue estimate failed");
+  for (int j = 0; j < kk; ++j) {
+    diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < kk) off[j] = std::sqrt(be[j]) / al[j];
+  }
+  *out = tridiag_max_eig(diag, off, kk);
+  return DG_OK;
+}
+
+size_t batch_gather_bytes(int n) { return up256(sizeof(double) * kGatherRow * (size_t)n); }
+
+// Descriptor bytes: the largest program (the V-cycle) with every level
+// smoothed by the longest polynomial, room for the six programs of an
+// outer iteration (two V-cycles among them) and the occasional residual
+// replacement, plus slack.
+size_t batch_arena_bytes(const dg_mesh* const* meshes, int n, const dg_solve_params* sp) {
+  const int d0 = std::max(1, sp->cheb_degree);
+  const int dc = sp->coarse_degree > 0 ? sp->coarse_degree : d0;
+  const size_t per_level = (size_t)(2 * std::max(d0, dc) + 4 * d0 + 8);
+  const size_t seg = std::max({sizeof(PoiSeg<double>), sizeof(TrSeg<double>), sizeof(VSeg)});
+  size_t segs = 0, levels = 0;
+  for (int i = 0; i < n; ++i) {
+    const int L = std::max(1, meshes[i]->mg_nlev);
+    segs += per_level * L + 64;
+    levels = std::max<size_t>(levels, (size_t)L);
+  }
+  // every launch aligns its table to 256 bytes; a V-cycle has at most
+  // ~per_level launches per level and degree group (5 groups)
+  const size_t launches = 5 * (per_level * levels + 64);
+  return up256(4 * (segs * seg + launches * 256) + (1 << 20));
+}
+
+int solve_batched(const dg_mesh* const* meshes, int n, const dg_solve_params* sp, const double* const* b,
+                  double* const* x, void* const* ws, const size_t* ws_bytes, dg_solve_stats* stats, int32_t* codes,
+                  void* bws, size_t bws_bytes, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  auto since = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+  if (!meshes || !sp || !b || !x || !ws || !ws_bytes || !bws || n < 1 || n > DG_MAX_BATCH)
+    return set_error(DG_ERR_ARG, "batched solve: NULL argument or batch size outside [1, DG_MAX_BATCH]");
+  if (!(sp->rtol > 0) || sp->cheb_degree < 1 || sp->coarse_degree < 0 || sp->max_outer < 1)
+    return set_error(DG_ERR_ARG, "invalid solve parameters");
+  if (!sp->multigrid) return set_error(DG_ERR_UNSUPPORTED, "batched solves run the multigrid preconditioner only");
+  for (int i = 0; i < n; ++i) {
+    const dg_mesh* m = meshes[i];
+    if (!m || !b[i] || !x[i] || !ws[i]) return set_error(DG_ERR_ARG, "batched solve: NULL mesh, vector or workspace");
+    if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Poisson operator is built for flat (box) meshes only");
+    if (m->mg_nlev < 2) return set_error(DG_ERR_UNSUPPORTED, "batched solve: a mesh has no coarser multigrid level");
+    if (ws_bytes[i] < solve_bytes(m)) return set_error(DG_ERR_WORKSPACE, "solve workspace too small");
+    if (b[i] == x[i]) return set_error(DG_ERR_ARG, "b and x must not alias");
+  }
+  const size_t gb = batch_gather_bytes(n);
+  const size_t ab = batch_arena_bytes(meshes, n, sp);
+  if (bws_bytes < gb + ab) return set_error(DG_ERR_WORKSPACE, "batched solve: descriptor workspace too small");
+  Batch B;
+  B.sp = sp;
+  B.s = s;
+  B.mixed = sp->mixed != 0;
+  B.deg0 = sp->cheb_degree;
+  B.degc = sp->coarse_degree > 0 ? sp->coarse_degree : sp->cheb_degree;
+  B.gather = static_cast<double*>(bws);
+  B.arena = static_cast<char*>(bws) + gb;
+  B.arena_cap = ab;
+  char* pin = nullptr;
+  if (int rc = pinned_get(ab + gb, &pin, &B.ev)) return rc;
+  B.stage = pin;
+  B.rb = reinterpret_cast<double*>(pin + ab);
+  B.I.resize(n);
+  Set all;
+  for (int i = 0; i < n; ++i) {
+    BInst& in = B.I[i];
+    in.m = meshes[i];
+    carve_solver(in.S, in.m, ws[i], s);
+    in.b = b[i];
+    in.x = x[i];
+    in.idx = i;
+    all.push_back(&in);
+  }
+  int rc;
+#define DG_TRY(expr) \
+  if ((rc = (expr))) return rc
+
+  // inverse diagonals of every level, b' = b - mean(b), ||b'||^2
+  Prog p0;
+  B.vop<V_RECIP64>(p0, all, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.d = in.S.dinv; g.a = in.m->diag; });
+  B.vop<V_RECIP32>(p0, all, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.d = in.S.dinv32; g.a = in.m->diag; });
+  for (int l = 1; l < kMaxLevels; ++l) {
+    Set sl;
+    for (BInst* in : all)
+      if (l < in->S.nlev) sl.push_back(in);
+    B.vop<V_RECIP64>(p0, sl, [l](VSeg& g, BInst& in) {
+      g.n = in.m->mg[l].n; g.d = in.S.lv[l].dinv64; g.a = in.m->mg[l].diag; });
+    B.vop<V_RECIP32>(p0, sl, [l](VSeg& g, BInst& in) {
+      g.n = in.m->mg[l].n; g.d = in.S.lv[l].dinv32; g.a = in.m->mg[l].diag; });
+  }
+  B.reduce<V_SUM>(p0, all, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.a = in.b; }, B_SUM);
+  B.vop<V_COPY_SUB_MEAN>(p0, all, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.d = in.S.bp; g.a = in.b; }, B_SUM);
+  B.reduce<V_DOT>(p0, all, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.a = in.S.bp; g.b = in.S.bp; }, B_NB);
+  DG_TRY(B.run(p0));
+
+  // Chebyshev intervals: Lanczos estimates of lmax(D^{-1} A_l), cached per mesh
+  for (int l = 0; l < kMaxLevels; ++l) {
+    Set need;
+    for (BInst* in : all) {
+      if (l >= in->S.nlev) continue;
+      dg_mesh* mm = const_cast<dg_mesh*>(in->m);
+      const bool want = l == 0 ? !(mm->lam_max > 0)
+                               : ((l < in->S.nlev - 1 || !mm->coarse_inv) && !(mm->mg[l].lam > 0));
+      if (want) need.push_back(in);
+    }
+    if (need.empty()) continue;
+    Prog pl;
+    B.lanczos(pl, need, l);
+    DG_TRY(B.run(pl));
+    DG_TRY(B.readback());
+    DG_TRY(B.wait());
+    for (BInst* in : need) {
+      dg_mesh* mm = const_cast<dg_mesh*>(in->m);
+      double lam = 0;
+      DG_TRY(lanczos_lmax(B.rb + (size_t)kGatherRow * in->idx, &lam));
+      if (l == 0) mm->lam_max = lam;
+      else mm->mg[l].lam = lam;
+    }
+  }
+  for (BInst* in : all) {
+    dg_mesh* mm = const_cast<dg_mesh*>(in->m);
+    mm->mg[0].lam = mm->lam_max;
+    in->applies64 = in->applies32 = 0;  // (the estimates are not part of the solve's count)
+  }
+  // ||b'|| of every mesh (read back after the eigenvalue estimates)
+  {
+    Prog pg;
+    B.gather_rows(pg, all, B_NB, 1);
+    DG_TRY(B.run(pg));
+    DG_TRY(B.readback());
+    DG_TRY(B.wait());
+  }
+  Set act;
+  {
+    Set zero;
+    for (BInst* in : all) {
+      in->nb = std::sqrt(B.rb[(size_t)kGatherRow * in->idx]);
+      if (!std::isfinite(in->nb)) {
+        in->code = set_error(DG_ERR_NONFINITE, "non-finite right-hand side");
+        in->done = true;
+      } else if (in->nb == 0.0) {
+        zero.push_back(in);
+        in->done = true;
+      } else {
+        act.push_back(in);
+      }
+    }
+    Prog pz;
+    B.vop<V_FILL>(pz, zero, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.d = in.x; });
+    DG_TRY(B.run(pz));
+  }
+  // x to zero mean, true residual of the initial guess
+  {
+    Prog pi;
+    B.project_x(pi, act);
+    B.true_residual(pi, act);
+    DG_TRY(B.run(pi));
+    DG_TRY(B.readback());
+    DG_TRY(B.wait());
+    Set keep;
+    for (BInst* in : act) {
+      in->rn = std::sqrt(B.rb[(size_t)kGatherRow * in->idx]);
+      if (!std::isfinite(in->rn)) {
+        in->code = set_error(DG_ERR_NONFINITE, "non-finite residual");
+        in->done = true;
+      } else if (in->rn <= sp->rtol * in->nb) {
+        in->done = true;
+        in->seconds = since();
+      } else {
+        keep.push_back(in);
+      }
+    }
+    act.swap(keep);
+    Prog pp;
+    B.precond_dots(pp, act, 0, false, -1, B_RZ0, -1);
+    B.vop<V_COPY>(pp, act, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.d = in.S.p; g.a = in.S.z; });
+    DG_TRY(B.run(pp));
+  }
+  // outer iterations in lockstep; programs are rebuilt when the set changes
+  const int replace_every = 50;
+  Prog pa[2], pb[2], pc[2];
+  bool built = false;
+  for (int it = 1; it <= sp->max_outer && !act.empty(); ++it) {
+    const int par = it & 1;                       // iteration parity: z and zold swap every iteration
+    const int cur = par ? B_RZ0 : B_RZ1, nxt = par ? B_RZ1 : B_RZ0;
+    const int zs = par ? 1 : 0, zos = par ? 0 : 1;  // 0: the buffer S.z, 1: S.zold
+    if (!built) {
+      for (int q = 0; q < 2; ++q) {
+        const int c = q ? B_RZ0 : B_RZ1, nx = q ? B_RZ1 : B_RZ0, z = q ? 1 : 0, zo = q ? 0 : 1;
+        pa[q] = Prog();
+        pb[q] = Prog();
+        pc[q] = Prog();
+        B.poi<double>(pa[q], kPlain, act, 0, [](PoiSeg<double>& g, BInst& in) { g.p = in.S.p; g.y = in.S.q; });
+        B.reduce<V_DOT>(pa[q], act, [](VSeg& g, BInst& in) { g.n = in.m->n_p; g.a = in.S.p; g.b = in.S.q; }, B_PQ);
+        const bool m32 = B.mixed;
+        B.vop<V_UPDATE_XR>(pa[q], act, [m32](VSeg& g, BInst& in) {
+          g.n = in.m->n_p; g.d = in.x; g.e = in.S.r; g.a = in.S.p; g.b = in.S.q;
+          g.c = m32 ? (const void*)in.S.r32 : nullptr;
+        }, c, B_PQ, B_RR, B_SCL);
+        B.vop<V_FINAL>(pa[q], act, [](VSeg& g, BInst& in) { g.n = vop_blocks(V_UPDATE_XR, in.m->n_p); }, B_RR);
+        B.gather_rows(pa[q], act, B_RR, 1);
+        B.precond_dots(pb[q], act, z, m32, zo, nx, B_RZX);
+        B.vop<V_UPDATE_P>(pc[q], act, [z](VSeg& g, BInst& in) {
+          g.n = in.m->n_p; g.d = in.S.p; g.a = z == 0 ? in.S.z : in.S.zold;
+        }, nx, B_RZX, c);
+      }
+      built = true;
+    }
+    DG_TRY(B.run(pa[par]));
+    DG_TRY(B.readback());
+    DG_TRY(B.run(pb[par]));   // queued behind the read-back; runs while the host waits
+    DG_TRY(B.wait());
+    Set check, failed;
+    for (BInst* in : act) {
+      in->it = it;
+      in->rn = std::sqrt(B.rb[(size_t)kGatherRow * in->idx]);
+      if (!std::isfinite(in->rn)) failed.push_back(in);
+      else if (in->rn <= sp->rtol * in->nb || it % replace_every == 0) check.push_back(in);
+    }
+    Set conv;
+    if (!check.empty()) {
+      Prog pt;
+      B.true_residual(pt, check);
+      DG_TRY(B.run(pt));
+      DG_TRY(B.readback());
+      DG_TRY(B.wait());
+      Set again;
+      for (BInst* in : check) {
+        in->rn = std::sqrt(B.rb[(size_t)kGatherRow * in->idx]);
+        if (!std::isfinite(in->rn)) failed.push_back(in);
+        else if (in->rn <= sp->rtol * in->nb) conv.push_back(in);
+        else again.push_back(in);
+      }
+      Prog pr;
+      B.precond_dots(pr, again, zs, false, zos, nxt, B_RZX);
+      DG_TRY(B.run(pr));
+    }
+    (void)cur;
+    DG_TRY(B.run(pc[par]));   // (harmless for the meshes that just converged)
+    for (BInst* in : failed) {
+      in->code = set_error(DG_ERR_NONFINITE, "non-finite residual");
+      in->done = true;
+    }
+    for (BInst* in : conv) {
+      in->done = true;
+      in->seconds = since();
+    }
+    if (!failed.empty() || !conv.empty()) {
+      Set keep;
+      for (BInst* in : act)
+        if (!in->done) keep.push_back(in);
+      act.swap(keep);
+      built = false;
+    }
+  }
+  for (BInst* in : act) {
+    in->code = set_error(DG_ERR_NOT_CONVERGED, "iteration cap reached");
+    in->seconds = since();
+  }
+  // zero-mean solutions
+  {
+    Set fin;
+    for (BInst& in : B.I)
+      if (in.code == DG_OK || in.code == DG_ERR_NOT_CONVERGED) fin.push_back(&in);
+    Prog pe;
+    B.project_x(pe, fin);
+    DG_TRY(B.run(pe));
+  }
+  DG_TRY(check_hip(hipStreamSynchronize(s), "batched solve synchronize"));
+  for (BInst& in : B.I) {
+    if (codes) codes[in.idx] = in.code;
+    if (stats) {
+      dg_solve_stats& st = stats[in.idx];
+      st = dg_solve_stats{};
+      st.outer_its = in.it;
+      st.op_applies_f64 = in.applies64;
+      st.op_applies_f32 = in.applies32;
+      st.rel_resid = in.nb > 0 ? in.rn / in.nb : 0.0;
+      st.seconds = in.seconds;
+    }
+  }
+#undef DG_TRY
+  return DG_OK;
+}
+
+}  // namespace
+
 // Solve workspace of dg_solve_poisson_noalloc: one copy per GPU, held until
 // the process ends.  In host code `scratch` only names the symbol; its device
 // address comes from hipGetSymbolAddress (scratch_address below).
@@ -820,6 +1870,22 @@ int dg_solve_poisson_noalloc(const dg_mesh* m, const dg_solve_params* sp, const 
   void* ws = nullptr;
   if (int rc = scratch_address(&ws)) return rc;
   return solve_poisson_ws(m, sp, b, x, ws, (size_t)DG_NOALLOC_SOLVE_MAX_BYTES, st, stream);
+}
+
+int64_t dg_solve_batch_workspace_bytes(const dg_mesh* const* meshes, int32_t n, const dg_solve_params* sp) {
+  if (!meshes || !sp || n < 1 || n > DG_MAX_BATCH)
+    return set_error(DG_ERR_ARG, "batched solve: NULL argument or batch size outside [1, DG_MAX_BATCH]");
+  for (int i = 0; i < n; ++i)
+    if (!meshes[i]) return set_error(DG_ERR_ARG, "batched solve: NULL mesh");
+  return (int64_t)(batch_gather_bytes(n) + batch_arena_bytes(meshes, n, sp));
+}
+
+int dg_solve_poisson_batched(const dg_mesh* const* meshes, int32_t n, const dg_solve_params* sp,
+                             const double* const* b, double* const* x, void* const* ws, const size_t* ws_bytes,
+                             dg_solve_stats* stats, int32_t* codes, void* batch_ws, size_t batch_ws_bytes,
+                             void* stream) {
+  return solve_batched(meshes, n, sp, b, x, ws, ws_bytes, stats, codes, batch_ws, batch_ws_bytes,
+                       static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
