@@ -497,7 +497,15 @@ def main():
         srv.update({"stream": f"{scfg.n_requests} requests, exponential gaps mean {scfg.mean_interarrival * 1e3:g} ms, "
                               f"grids {list(scfg.grids)}, k {list(scfg.degrees)}, k_p = k-1, "
                               f"{scfg.applies} velocity applies + 1 mixed solve (1e-10) each",
-                    "budget_bytes": 32 << 30, "slots": 64})
+                    "budget_bytes": 32 << 30, "slots": 64, "solves": "batched per velocity round"})
+        # the same stream with one solve call per request, and both with every
+        # request arriving at once (throughput under a full queue)
+        keys = ("makespan_s", "dofs_per_s", "latency_p50_ms", "latency_p99_ms", "latency_max_ms")
+        one = Server(applies=scfg.applies, device=dev, batch_solves=False).run(reqs).summary()
+        srv["unbatched_solves"] = {k: one[k] for k in keys}
+        for bs in (True, False):
+            burst = Server(applies=scfg.applies, device=dev, batch_solves=bs).run(reqs, time_scale=0.0).summary()
+            srv["burst_" + ("batched" if bs else "unbatched")] = {k: burst[k] for k in keys}
         extras["serving"] = srv
         print(f"bench: serving done in {rep.makespan:.2f} s", file=sys.stderr, flush=True)
     if args.copy_calibration:

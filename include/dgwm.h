@@ -221,8 +221,10 @@ int64_t dg_batch_workspace_bytes(int32_t n);
  *   workspace:    device, 256-byte aligned, >= dg_batch_workspace_bytes(n);
  *                 it holds the launch descriptors, so it must not be reused
  *                 before the launches on `stream` have run.
- *   The call stages the descriptors with a copy and waits for `stream` to
- *   reach it (work queued earlier on `stream` is waited for too).
+ *   The descriptors go up with one asynchronous copy from pinned staging
+ *   owned by the calling thread (8 slots used round-robin, allocated on
+ *   first use and kept for the thread's lifetime); the call waits only when
+ *   the copy that last used its slot, 8 calls earlier, has not yet run.
  *   Errors: DG_ERR_ARG, DG_ERR_WORKSPACE, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
 int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, dg_prec prec, const void* const* u,
                                        void* const* r, void* workspace, size_t ws_bytes, void* stream);
@@ -483,8 +485,8 @@ int dg_solve_poisson(const dg_mesh* mesh, const dg_solve_params* sp, const doubl
 int dg_solve_poisson_noalloc(const dg_mesh* mesh, const dg_solve_params* sp, const double* b, double* x,
                              dg_solve_stats* stats, void* stream);
 
-/* Device bytes of the descriptor workspace of a batched solve over these
- * n meshes with these parameters, or a negative DG_ERR_* code. */
+/* Device bytes of the workspace of a batched solve over these n meshes
+ * with these parameters, or a negative DG_ERR_* code. */
 int64_t dg_solve_batch_workspace_bytes(const dg_mesh* const* meshes, int32_t n, const dg_solve_params* sp);
 
 /* The solves of n independent meshes (the serving path: one pressure step,
@@ -495,12 +497,13 @@ int64_t dg_solve_batch_workspace_bytes(const dg_mesh* const* meshes, int32_t n, 
  * vector updates and reductions), from descriptor tables kept in batch_ws
  * while the set of unconverged meshes is unchanged.  A mesh leaves the batch
  * when it converges.  Per mesh the method and the stopping rule are those of
- * dg_solve_poisson with multigrid = 1, and its arithmetic does not depend on
- * the other meshes of the batch: a mesh gives bit-for-bit the same x and
- * statistics in any batch, alone included (reductions use a block count set
- * by the vector length; results may differ from dg_solve_poisson's in the
- * last bits).  Eigenvalue estimates missing from a mesh's cache are computed
- * for all such meshes together at the start.  One host read-back per outer
+ * dg_solve_poisson with multigrid = 1, step by step with the same kernel
+ * bodies and reduction layout (a block count set by the vector length): a
+ * mesh gets bit-for-bit the x and statistics of dg_solve_poisson, in any
+ * batch.  Descriptors travel in kernel
+ * arguments (up to 8 to 32 meshes per launch; larger batches take several).
+ * Eigenvalue estimates missing from a mesh's cache are computed for all such
+ * meshes together at the start.  One host read-back per outer
  * iteration for the whole batch, through pinned memory owned by the calling
  * thread (allocated on its first call and kept for the thread's lifetime).
  *   meshes, b, x, ws, ws_bytes: host arrays of n entries; b[i], x[i] device
@@ -510,11 +513,12 @@ int64_t dg_solve_batch_workspace_bytes(const dg_mesh* const* meshes, int32_t n, 
  *   sp: shared parameters (multigrid must be 1);
  *   stats, codes: host arrays of n entries (may be NULL): per mesh
  *     statistics and status (DG_OK, DG_ERR_NOT_CONVERGED, DG_ERR_NONFINITE);
- *   batch_ws: device, >= dg_solve_batch_workspace_bytes(meshes, n, sp).
+ *   batch_ws: device, >= dg_solve_batch_workspace_bytes(meshes, n, sp)
+ *     (one row of read-back scalars per mesh).
  * Returns DG_OK when the batch ran (per mesh outcomes in codes), else
  * DG_ERR_ARG, DG_ERR_WORKSPACE, DG_ERR_UNSUPPORTED (multigrid = 0, a curved
  * mesh or one without a coarser level) or DG_ERR_HIP.  Calls on one thread
- * must not overlap (they share its pinned staging); the call returns after
+ * must not overlap (they share its pinned read-back rows); the call returns after
  * the stream has drained. */
 int dg_solve_poisson_batched(const dg_mesh* const* meshes, int32_t n, const dg_solve_params* sp,
                              const double* const* b, double* const* x, void* const* ws, const size_t* ws_bytes,

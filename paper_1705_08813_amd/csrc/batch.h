@@ -1,9 +1,10 @@
-// Batched launches over many independent meshes (the serving path): one
-// segment per mesh (or mesh level) in a device-resident descriptor table,
-// the workgroups of the launch dealt to the segments in order.  Segment s
-// owns the blocks [blk0_s, blk0_{s+1}); blk0_0 = 0.  Every segment runs the
-// same code as the single-mesh launch, so its results do not depend on the
-// other segments of the launch.
+// Batched launches over many independent meshes (the serving path): the
+// descriptors of up to K meshes (or mesh levels) travel by value in the
+// kernel arguments of one launch, the workgroups of the launch dealt to
+// them in order; larger batches take ceil(n / K) launches.  Segment s owns
+// the blocks [blk0_s, blk0_{s+1}); blk0_0 = 0.  A mesh's segment runs the
+// same compiled code in every launch it appears in, so its results do not
+// depend on the other segments of the launch or on the batch.
 #pragma once
 
 #include "kern_common.h"
@@ -73,13 +74,21 @@ struct DenseSeg {
   int64_t blk0;
 };
 
+// Segments per launch (kernel arguments stay below 4 KiB).
+constexpr int kPoiSegs = 8, kTrSegs = 16, kDenseSegs = 32;
+template <typename S, int K>
+struct SegArr {
+  S s[K];
+  int n;
+};
+
 // Segment that owns block `bid` (segments sorted by blk0).
-template <typename S>
-__device__ __forceinline__ int find_seg(const S* __restrict__ segs, int nseg, int64_t bid) {
-  int lo = 0, hi = nseg - 1;
+template <typename S, int K>
+__device__ __forceinline__ int find_seg(const SegArr<S, K>& a, int64_t bid) {
+  int lo = 0, hi = a.n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (segs[mid].blk0 <= bid) lo = mid;
+    if (a.s[mid].blk0 <= bid) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -94,13 +103,16 @@ bool mg_full_transfer(const dg_mesh* m, int l);
 int mg_cells_per_block(int np, bool full);
 int dense_rows_per_block();
 
+// The launchers take host arrays of segments (blk0 is filled in per launch)
+// of one degree (and transfer family) and split them into launches of at
+// most K segments.
 template <typename T>
-int launch_poisson_batched(int np, int kind, const PoiSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s);
+int launch_poisson_batched(int np, int kind, const PoiSeg<T>* segs, int nseg, hipStream_t s);
 template <typename T>
-int launch_mg_restrict_batched(int np, bool full, const TrSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s);
+int launch_mg_restrict_batched(int np, bool full, const TrSeg<T>* segs, int nseg, hipStream_t s);
 template <typename T>
-int launch_mg_prolong_batched(int np, bool full, const TrSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s);
+int launch_mg_prolong_batched(int np, bool full, const TrSeg<T>* segs, int nseg, hipStream_t s);
 template <typename T>
-int launch_dense_batched(const DenseSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s);
+int launch_dense_batched(const DenseSeg<T>* segs, int nseg, hipStream_t s);
 
 }  // namespace dgwm

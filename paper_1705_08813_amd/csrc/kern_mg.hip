@@ -474,9 +474,9 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(int n, const T* __rest
 }
 
 template <typename T, int NP, bool FULL, bool RESTRICT>
-__global__ __launch_bounds__(256) void mg_transfer_batched(const TrSeg<T>* __restrict__ segs, int nseg) {
-  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
-  const TrSeg<T>& S = segs[si];
+__global__ __launch_bounds__(256) void mg_transfer_batched(const SegArr<TrSeg<T>, kTrSegs> a) {
+  const int si = find_seg(a, (int64_t)blockIdx.x);
+  const TrSeg<T>& S = a.s[si];
   const int64_t blk = (int64_t)blockIdx.x - S.blk0;
   if (FULL) {
     if (RESTRICT) mg_restrict_full_body<T, NP>(S.tr, S.ncc, blk, S.in, S.out);
@@ -488,9 +488,9 @@ __global__ __launch_bounds__(256) void mg_transfer_batched(const TrSeg<T>* __res
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void dense_apply_batched(const DenseSeg<T>* __restrict__ segs, int nseg) {
-  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
-  const DenseSeg<T>& S = segs[si];
+__global__ __launch_bounds__(256) void dense_apply_batched(const SegArr<DenseSeg<T>, kDenseSegs> a) {
+  const int si = find_seg(a, (int64_t)blockIdx.x);
+  const DenseSeg<T>& S = a.s[si];
   dense_apply_body<T>((int)S.n, (int64_t)blockIdx.x - S.blk0, S.B, S.b, S.x);
 }
 
@@ -543,47 +543,73 @@ int mg_cells_per_block(int np, bool full) {
 int dense_rows_per_block() { return 4; }
 
 template <typename T>
-static int launch_mg_batched(int np, bool full, bool restrict_, const TrSeg<T>* segs, int nseg, int64_t nblk,
-                             hipStream_t s) {
-  if (nseg <= 0 || nblk <= 0) return DG_OK;
-#define X(a)                                                                                                   \
-  if (np == a) {                                                                                               \
-    const dim3 g((unsigned)nblk);                                                                              \
-    if (full && restrict_)                                                                                     \
-      hipLaunchKernelGGL((mg_transfer_batched<T, a, true, true>), g, dim3(256), 0, s, segs, nseg);              \
-    else if (full)                                                                                             \
-      hipLaunchKernelGGL((mg_transfer_batched<T, a, true, false>), g, dim3(256), 0, s, segs, nseg);             \
-    else if (restrict_)                                                                                        \
-      hipLaunchKernelGGL((mg_transfer_batched<T, a, false, true>), g, dim3(256), 0, s, segs, nseg);             \
-    else                                                                                                       \
-      hipLaunchKernelGGL((mg_transfer_batched<T, a, false, false>), g, dim3(256), 0, s, segs, nseg);            \
-    return check_hip(hipGetLastError(), "batched transfer launch");                                            \
-  }
-  DG_MG_NP(X)
+static int launch_mg_batched(int np, bool full, bool restrict_, const TrSeg<T>* segs, int nseg, hipStream_t s) {
+  const int cpc = mg_cells_per_block(np, full);
+  if (cpc <= 0) return set_error(DG_ERR_UNSUPPORTED, "multigrid transfer degree not compiled");
+  for (int c0 = 0; c0 < nseg; c0 += kTrSegs) {
+    SegArr<TrSeg<T>, kTrSegs> a{};
+    a.n = std::min(kTrSegs, nseg - c0);
+    int64_t blk = 0;
+    for (int i = 0; i < a.n; ++i) {
+      a.s[i] = segs[c0 + i];
+      a.s[i].blk0 = blk;
+      blk += (a.s[i].ncc + cpc - 1) / cpc;
+    }
+    if (blk == 0) continue;
+    const dim3 g((unsigned)blk);
+    bool done = false;
+#define X(q)                                                                                                   \
+    if (np == q) {                                                                                             \
+      done = true;                                                                                             \
+      if (full && restrict_)                                                                                   \
+        hipLaunchKernelGGL((mg_transfer_batched<T, q, true, true>), g, dim3(256), 0, s, a);                     \
+      else if (full)                                                                                           \
+        hipLaunchKernelGGL((mg_transfer_batched<T, q, true, false>), g, dim3(256), 0, s, a);                    \
+      else if (restrict_)                                                                                      \
+        hipLaunchKernelGGL((mg_transfer_batched<T, q, false, true>), g, dim3(256), 0, s, a);                    \
+      else                                                                                                     \
+        hipLaunchKernelGGL((mg_transfer_batched<T, q, false, false>), g, dim3(256), 0, s, a);                   \
+    }
+    DG_MG_NP(X)
 #undef X
-  return set_error(DG_ERR_UNSUPPORTED, "multigrid transfer degree not compiled");
+    if (!done) return set_error(DG_ERR_UNSUPPORTED, "multigrid transfer degree not compiled");
+    if (int rc = check_hip(hipGetLastError(), "batched transfer launch")) return rc;
+  }
+  return DG_OK;
 }
 
 template <typename T>
-int launch_mg_restrict_batched(int np, bool full, const TrSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
-  return launch_mg_batched<T>(np, full, true, segs, nseg, nblk, s);
+int launch_mg_restrict_batched(int np, bool full, const TrSeg<T>* segs, int nseg, hipStream_t s) {
+  return launch_mg_batched<T>(np, full, true, segs, nseg, s);
 }
 template <typename T>
-int launch_mg_prolong_batched(int np, bool full, const TrSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
-  return launch_mg_batched<T>(np, full, false, segs, nseg, nblk, s);
+int launch_mg_prolong_batched(int np, bool full, const TrSeg<T>* segs, int nseg, hipStream_t s) {
+  return launch_mg_batched<T>(np, full, false, segs, nseg, s);
 }
 template <typename T>
-int launch_dense_batched(const DenseSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
-  if (nseg <= 0 || nblk <= 0) return DG_OK;
-  hipLaunchKernelGGL((dense_apply_batched<T>), dim3((unsigned)nblk), dim3(256), 0, s, segs, nseg);
-  return check_hip(hipGetLastError(), "batched dense apply launch");
+int launch_dense_batched(const DenseSeg<T>* segs, int nseg, hipStream_t s) {
+  const int rpb = dense_rows_per_block();
+  for (int c0 = 0; c0 < nseg; c0 += kDenseSegs) {
+    SegArr<DenseSeg<T>, kDenseSegs> a{};
+    a.n = std::min(kDenseSegs, nseg - c0);
+    int64_t blk = 0;
+    for (int i = 0; i < a.n; ++i) {
+      a.s[i] = segs[c0 + i];
+      a.s[i].blk0 = blk;
+      blk += (a.s[i].n + rpb - 1) / rpb;
+    }
+    if (blk == 0) continue;
+    hipLaunchKernelGGL((dense_apply_batched<T>), dim3((unsigned)blk), dim3(256), 0, s, a);
+    if (int rc = check_hip(hipGetLastError(), "batched dense apply launch")) return rc;
+  }
+  return DG_OK;
 }
-template int launch_mg_restrict_batched<double>(int, bool, const TrSeg<double>*, int, int64_t, hipStream_t);
-template int launch_mg_restrict_batched<float>(int, bool, const TrSeg<float>*, int, int64_t, hipStream_t);
-template int launch_mg_prolong_batched<double>(int, bool, const TrSeg<double>*, int, int64_t, hipStream_t);
-template int launch_mg_prolong_batched<float>(int, bool, const TrSeg<float>*, int, int64_t, hipStream_t);
-template int launch_dense_batched<double>(const DenseSeg<double>*, int, int64_t, hipStream_t);
-template int launch_dense_batched<float>(const DenseSeg<float>*, int, int64_t, hipStream_t);
+template int launch_mg_restrict_batched<double>(int, bool, const TrSeg<double>*, int, hipStream_t);
+template int launch_mg_restrict_batched<float>(int, bool, const TrSeg<float>*, int, hipStream_t);
+template int launch_mg_prolong_batched<double>(int, bool, const TrSeg<double>*, int, hipStream_t);
+template int launch_mg_prolong_batched<float>(int, bool, const TrSeg<float>*, int, hipStream_t);
+template int launch_dense_batched<double>(const DenseSeg<double>*, int, hipStream_t);
+template int launch_dense_batched<float>(const DenseSeg<float>*, int, hipStream_t);
 
 int launch_mg_restrict(const dg_mesh* m, int l, dg_prec prec, const void* rf, void* rc, hipStream_t s) {
   const Tr tr = mg_transfer_geometry(m, l);

@@ -7,6 +7,8 @@
 // One workgroup per cell, sum-factorized volume term, element-by-element
 // face terms (each cell reads its neighbour's nodal values), single writer
 // per output entry.
+#include <algorithm>
+
 #include "batch.h"
 
 namespace dgwm {
@@ -334,12 +336,12 @@ __global__ __launch_bounds__(256) void poisson_kernel(const MeshDev M, const T* 
   poisson_body<T, NP, KIND>(M, p, y, ncell, blk, E);
 }
 
-// One launch over the segments of many meshes (cells of each segment in
-// order; small meshes, so no XCD remapping).
+// One launch over the segments of up to kPoiSegs meshes (cells of each
+// segment in order; small meshes, so no XCD remapping).
 template <typename T, int NP, int KIND>
-__global__ __launch_bounds__(256) void poisson_kernel_batched(const PoiSeg<T>* __restrict__ segs, int nseg) {
-  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
-  const PoiSeg<T>& S = segs[si];
+__global__ __launch_bounds__(256) void poisson_kernel_batched(const SegArr<PoiSeg<T>, kPoiSegs> a) {
+  const int si = find_seg(a, (int64_t)blockIdx.x);
+  const PoiSeg<T>& S = a.s[si];
   poisson_body<T, NP, KIND>(S.M, S.p, S.y, S.ncell, (int)((int64_t)blockIdx.x - S.blk0), S.E);
 }
 
@@ -452,35 +454,40 @@ int poisson_cells_per_block(int np) {
 }
 
 template <typename T>
-int launch_poisson_batched(int np, int kind, const PoiSeg<T>* segs, int nseg, int64_t nblk, hipStream_t s) {
-  if (nseg <= 0 || nblk <= 0) return DG_OK;
-#define X(a, b)                                                                                                \
-  if (np == a) {                                                                                               \
-    switch (kind) {                                                                                            \
-      case kPlain:                                                                                             \
-        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kPlain>), dim3((unsigned)nblk), dim3(256), 0, s, segs,  \
-                           nseg);                                                                              \
-        break;                                                                                                 \
-      case kResid:                                                                                             \
-        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kResid>), dim3((unsigned)nblk), dim3(256), 0, s, segs,  \
-                           nseg);                                                                              \
-        break;                                                                                                 \
-      case kCheb:                                                                                              \
-        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kCheb>), dim3((unsigned)nblk), dim3(256), 0, s, segs,   \
-                           nseg);                                                                              \
-        break;                                                                                                 \
-      default:                                                                                                 \
-        hipLaunchKernelGGL((poisson_kernel_batched<T, a, kChebFirst>), dim3((unsigned)nblk), dim3(256), 0, s,    \
-                           segs, nseg);                                                                        \
-    }                                                                                                          \
-    return check_hip(hipGetLastError(), "batched poisson kernel launch");                                      \
-  }
-  DG_POI_COMBOS(X)
+int launch_poisson_batched(int np, int kind, const PoiSeg<T>* segs, int nseg, hipStream_t s) {
+  const int cb = poisson_cells_per_block(np);
+  if (cb <= 0) return set_error(DG_ERR_UNSUPPORTED, "poisson degree not compiled");
+  for (int c0 = 0; c0 < nseg; c0 += kPoiSegs) {
+    SegArr<PoiSeg<T>, kPoiSegs> a{};
+    a.n = std::min(kPoiSegs, nseg - c0);
+    int64_t blk = 0;
+    for (int i = 0; i < a.n; ++i) {
+      a.s[i] = segs[c0 + i];
+      a.s[i].blk0 = blk;
+      blk += (a.s[i].ncell + cb - 1) / cb;
+    }
+    if (blk == 0) continue;
+    const dim3 g((unsigned)blk);
+    bool done = false;
+#define X(q, b)                                                                                               \
+    if (np == q) {                                                                                            \
+      done = true;                                                                                            \
+      switch (kind) {                                                                                         \
+        case kPlain: hipLaunchKernelGGL((poisson_kernel_batched<T, q, kPlain>), g, dim3(256), 0, s, a); break; \
+        case kResid: hipLaunchKernelGGL((poisson_kernel_batched<T, q, kResid>), g, dim3(256), 0, s, a); break; \
+        case kCheb: hipLaunchKernelGGL((poisson_kernel_batched<T, q, kCheb>), g, dim3(256), 0, s, a); break;   \
+        default: hipLaunchKernelGGL((poisson_kernel_batched<T, q, kChebFirst>), g, dim3(256), 0, s, a);        \
+      }                                                                                                       \
+    }
+    DG_POI_COMBOS(X)
 #undef X
-  return set_error(DG_ERR_UNSUPPORTED, "poisson degree not compiled");
+    if (!done) return set_error(DG_ERR_UNSUPPORTED, "poisson degree not compiled");
+    if (int rc = check_hip(hipGetLastError(), "batched poisson kernel launch")) return rc;
+  }
+  return DG_OK;
 }
-template int launch_poisson_batched<double>(int, int, const PoiSeg<double>*, int, int64_t, hipStream_t);
-template int launch_poisson_batched<float>(int, int, const PoiSeg<float>*, int, int64_t, hipStream_t);
+template int launch_poisson_batched<double>(int, int, const PoiSeg<double>*, int, hipStream_t);
+template int launch_poisson_batched<float>(int, int, const PoiSeg<float>*, int, hipStream_t);
 
 bool poisson_supported(int np, int nq) {
 #define X(a, b) \

@@ -12,6 +12,8 @@
 // atomics are needed.  Enriched cells run a separate instantiation whose
 // wall-normal rule has NQY points and which reads the precomputed psi and
 // grad psi tables.
+#include <cstring>
+
 #include "kern_common.h"
 
 namespace dgwm {
@@ -1883,6 +1885,53 @@ int64_t batch_workspace_bytes(int n) {
 
 // Groups the meshes by compiled combination and launches one batched kernel
 // per group and cell class (regular / enriched).
+namespace {
+
+// Pinned staging ring of the batched call, per host thread: each call
+// takes the next slot, first waiting for the copy that last used it (long
+// done unless kStageSlots calls are still queued), and marks its own copy
+// with the slot's event.
+constexpr int kStageSlots = 8;
+struct StageRing {
+  char* p[kStageSlots] = {};
+  size_t cap[kStageSlots] = {};
+  hipEvent_t ev[kStageSlots] = {};
+  bool used[kStageSlots] = {};
+  int next = 0, cur = -1;
+};
+thread_local StageRing tl_ring;
+
+int stage_slot(size_t bytes, char** out) {
+  StageRing& R = tl_ring;
+  const int k = R.next;
+  R.next = (k + 1) % kStageSlots;
+  if (!R.ev[k] && hipEventCreateWithFlags(&R.ev[k], hipEventDisableTiming) != hipSuccess)
+    return set_error(DG_ERR_HIP, "staging event creation failed");
+  if (R.used[k])
+    if (int rc = check_hip(hipEventSynchronize(R.ev[k]), "staging slot reuse")) return rc;
+  if (R.cap[k] < bytes) {
+    if (R.p[k]) (void)hipHostFree(R.p[k]);
+    R.p[k] = nullptr;
+    R.cap[k] = 0;
+    void* q = nullptr;
+    const size_t want = std::max<size_t>(bytes, 64 << 10);
+    if (int rc = check_hip(hipHostMalloc(&q, want, hipHostMallocDefault), "pinned staging")) return rc;
+    R.p[k] = static_cast<char*>(q);
+    R.cap[k] = want;
+  }
+  R.cur = k;
+  *out = R.p[k];
+  return DG_OK;
+}
+
+int stage_release(hipStream_t s) {
+  StageRing& R = tl_ring;
+  R.used[R.cur] = true;
+  return check_hip(hipEventRecord(R.ev[R.cur], s), "staging event");
+}
+
+}  // namespace
+
 int launch_velocity_batched(const dg_mesh* const* meshes, int n, dg_prec prec, const void* const* u, void* const* r,
                             void* ws, size_t ws_bytes, hipStream_t s) {
   if ((int64_t)ws_bytes < batch_workspace_bytes(n)) return set_error(DG_ERR_WORKSPACE, "batch workspace too small");
@@ -1936,16 +1985,19 @@ int launch_velocity_batched(const dg_mesh* const* meshes, int n, dg_prec prec, c
     groups.push_back(G);
   }
   char* base = static_cast<char*>(ws);
+  const size_t items_bytes = (items.size() * sizeof(VelBatchItem) + 255) & ~size_t(255);
   VelBatchItem* d_items = reinterpret_cast<VelBatchItem*>(base);
-  int64_t* d_pre = reinterpret_cast<int64_t*>(base + ((items.size() * sizeof(VelBatchItem) + 255) & ~size_t(255)));
-  int rc = DG_OK;
-  if (!items.empty())
-    rc = check_hip(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(VelBatchItem), hipMemcpyHostToDevice, s),
-                   "batch items");
-  if (!rc) rc = check_hip(hipMemcpyAsync(d_pre, pre.data(), pre.size() * sizeof(int64_t), hipMemcpyHostToDevice, s),
-                          "batch prefixes");
-  // the staging vectors are released on return: wait for the copies
-  if (!rc) rc = check_hip(hipStreamSynchronize(s), "batch staging");
+  int64_t* d_pre = reinterpret_cast<int64_t*>(base + items_bytes);
+  // descriptors and prefixes go up in one copy from a pinned staging slot
+  // (no host wait: the slot is reused only after its copy has run)
+  char* stage = nullptr;
+  int rc = stage_slot(items_bytes + pre.size() * sizeof(int64_t), &stage);
+  if (rc) return rc;
+  if (!items.empty()) std::memcpy(stage, items.data(), items.size() * sizeof(VelBatchItem));
+  std::memcpy(stage + items_bytes, pre.data(), pre.size() * sizeof(int64_t));
+  rc = check_hip(hipMemcpyAsync(base, stage, items_bytes + pre.size() * sizeof(int64_t), hipMemcpyHostToDevice, s),
+                 "batch descriptors");
+  if (!rc) rc = stage_release(s);
   if (rc) return rc;
   for (const Group& G : groups) {
     bool done = false;

@@ -33,9 +33,14 @@ namespace dgwm {
 
 namespace {
 
-constexpr int kRedBlocks = 2048;  // eight blocks per CU keep enough loads in flight
+constexpr int kRedBlocks = 2048;  // most partial sums of one reduction (workspace sizing)
 constexpr double kSmoothRange = 20.0;  // multigrid smoother interval [lmax / 20, 1.1 lmax]
 constexpr int kRedThreads = 256;
+
+// Workgroups of a reduction over n entries: a function of n only, so that a
+// vector's partial sums, and hence its result, do not depend on the launch
+// (single solve or batch); about one entry per thread for small vectors.
+inline int red_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, 1024)); }
 
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(kRedThreads) void k_dot(const TA* __restrict__ a, c
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// a.b1 and a.b2 in one pass (partials of the second at part + kRedBlocks)
+// a.b1 and a.b2 in one pass (partials of the second at part + gridDim.x)
 __global__ __launch_bounds__(kRedThreads) void k_dot2(const double* __restrict__ a, const double* __restrict__ b1,
                                                       const double* __restrict__ b2, int64_t n,
                                                       double* __restrict__ part) {
@@ -76,7 +81,7 @@ __global__ __launch_bounds__(kRedThreads) void k_dot2(const double* __restrict__
   v2 = block_reduce(v2, sh);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = v1;
-    part[kRedBlocks + blockIdx.x] = v2;
+    part[gridDim.x + blockIdx.x] = v2;
   }
 }
 
@@ -90,19 +95,19 @@ __global__ __launch_bounds__(kRedThreads) void k_sum(const T* __restrict__ a, in
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// out[j] = sum of the kRedBlocks partials at part + j kRedBlocks, j < nout
-// (one block, fixed order).
-__global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict__ part, double* __restrict__ out,
-                                                       double* __restrict__ out2) {
+// *out = sum of the nb partials at part, *out2 (if not null) of the nb at
+// part + nb (one block, fixed order).
+__global__ __launch_bounds__(kRedThreads) void k_final(const double* __restrict__ part, int nb,
+                                                       double* __restrict__ out, double* __restrict__ out2) {
   __shared__ double sh[kRedThreads / 64];
   double v = 0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
   v = block_reduce(v, sh);
   if (threadIdx.x == 0) *out = v;
   if (!out2) return;
   __syncthreads();
   v = 0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[kRedBlocks + i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[nb + i];
   v = block_reduce(v, sh);
   if (threadIdx.x == 0) *out2 = v;
 }
@@ -206,7 +211,7 @@ __global__ void k_from_f32(double* __restrict__ z, const float* __restrict__ x, 
 }
 
 // z = scl * x32 together with the partial sums of r.z and (zold != nullptr)
-// r.zold (second set at part + kRedBlocks)
+// r.zold (second set at part + gridDim.x)
 __global__ __launch_bounds__(kRedThreads) void k_from_f32_dot2(double* __restrict__ z, const float* __restrict__ x,
                                                                const double* __restrict__ scl,
                                                                const double* __restrict__ r,
@@ -226,7 +231,7 @@ __global__ __launch_bounds__(kRedThreads) void k_from_f32_dot2(double* __restric
   v2 = block_reduce(v2, sh);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = v1;
-    part[kRedBlocks + blockIdx.x] = v2;
+    part[gridDim.x + blockIdx.x] = v2;
   }
 }
 
@@ -293,25 +298,32 @@ struct Solver {
   double *bp, *r, *z, *zold, *p, *q, *d64, *t64, *dinv, *sc, *part;
   float *r32, *z32, *d32, *t32, *x32, *rr32, *pp32, *qq32, *dinv32;
   int applies64 = 0, applies32 = 0, inner_total = 0;
+  int nred = 1;  // partials of the last reduction launched
 
+  // workgroups of a reduction over nn entries (remembered for red_final)
+  unsigned red(int64_t nn) {
+    nred = red_blocks(nn);
+    return (unsigned)nred;
+  }
   int red_final(double* out, double* out2 = nullptr) {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, s, part, out, out2);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedThreads), 0, s, part, nred, out, out2);
     return check_hip(hipGetLastError(), "reduce");
   }
   // a.b1 -> out1, a.b2 -> out2 in one pass over a
   int dot2(const double* a, const double* b1, const double* b2, double* out1, double* out2) {
-    hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b1, b2, n, part);
+    hipLaunchKernelGGL(k_dot2, dim3(red(n)), dim3(kRedThreads), 0, s, a, b1, b2, n, part);
     return red_final(out1, out2);
   }
   template <typename TA, typename TB>
   int dot(const TA* a, const TB* b, double* out, int64_t nn = -1) {
-    hipLaunchKernelGGL((k_dot<TA, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, nn < 0 ? n : nn, part);
+    if (nn < 0) nn = n;
+    hipLaunchKernelGGL((k_dot<TA, TB>), dim3(red(nn)), dim3(kRedThreads), 0, s, a, b, nn, part);
     return red_final(out);
   }
   template <typename T>
   int project(T* a, double* sum, int64_t nn = -1) {
     if (nn < 0) nn = n;
-    hipLaunchKernelGGL((k_sum<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, nn, part);
+    hipLaunchKernelGGL((k_sum<T>), dim3(red(nn)), dim3(kRedThreads), 0, s, a, nn, part);
     int rc = red_final(sum);
     if (rc) return rc;
     hipLaunchKernelGGL((k_sub_mean<T>), dim3(grid_of(nn)), dim3(256), 0, s, a, nn, sum);
@@ -497,7 +509,7 @@ int Solver::lanczos(int l, double* out) {
                          RZ + k - 1);
     if ((rc = launch_poisson_level(m, l, DG_F64, p, q, s))) return rc;
     if ((rc = dot(p, q, PQ + k, nn))) return rc;
-    hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, t64, r, p, q, nn, RZ + k,
+    hipLaunchKernelGGL((k_update_xr<double>), dim3(red(nn)), dim3(kRedThreads), 0, s, t64, r, p, q, nn, RZ + k,
                        PQ + k, part, (float*)nullptr, (const double*)nullptr, (double*)nullptr);
   }
   double h[2 * K];
@@ -629,7 +641,7 @@ int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* 
   const int degc = sp->coarse_degree > 0 ? sp->coarse_degree : deg;
 
   // b' = b - mean(b), ||b'||
-  hipLaunchKernelGGL((k_sum<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, b, S.n, S.part);
+  hipLaunchKernelGGL((k_sum<double>), dim3(S.red(S.n)), dim3(kRedThreads), 0, S.s, b, S.n, S.part);
   DG_TRY(S.red_final(sc + SUM));
   hipLaunchKernelGGL(k_copy_sub_mean, dim3(S.grid), dim3(256), 0, S.s, S.bp, b, S.n, sc + SUM);
   DG_TRY(S.dot(S.bp, S.bp, sc + NB));
@@ -675,7 +687,7 @@ int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* 
       for (int j = 0; j < sp->max_inner; ++j) {
         if ((e = S.A32(S.pp32, S.qq32))) return e;
         if ((e = S.dot(S.pp32, S.qq32, sc + IPQ))) return e;
-        hipLaunchKernelGGL((k_update_xr<float>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, S.x32, S.rr32, S.pp32,
+        hipLaunchKernelGGL((k_update_xr<float>), dim3(S.red(S.n)), dim3(kRedThreads), 0, S.s, S.x32, S.rr32, S.pp32,
                            S.qq32, S.n, sc + cur, sc + IPQ, S.part, (float*)nullptr, (const double*)nullptr,
                            (double*)nullptr);
         ++S.inner_total;
@@ -697,7 +709,7 @@ int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* 
     int e = precond(zz, r32_ready);
     if (e) return e;
     if (!sp->mixed) return zold ? S.dot2(S.r, zz, zold, rz, rzx) : S.dot(S.r, zz, rz);
-    hipLaunchKernelGGL(k_from_f32_dot2, dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, zz, S.x32, sc + SCL, S.r, zold,
+    hipLaunchKernelGGL(k_from_f32_dot2, dim3(S.red(S.n)), dim3(kRedThreads), 0, S.s, zz, S.x32, sc + SCL, S.r, zold,
                        S.n, S.part);
     return S.red_final(rz, zold ? rzx : nullptr);
   };
@@ -722,7 +734,7 @@ int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* 
     for (it = 1; it <= max_it; ++it) {
       DG_TRY(S.A64(S.p, S.q));
       DG_TRY(S.dot(S.p, S.q, sc + PQ));
-      hipLaunchKernelGGL((k_update_xr<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, S.s, x, S.r, S.p, S.q, S.n,
+      hipLaunchKernelGGL((k_update_xr<double>), dim3(S.red(S.n)), dim3(kRedThreads), 0, S.s, x, S.r, S.p, S.q, S.n,
                          sc + cur, sc + PQ, S.part, fused32 ? S.r32 : (float*)nullptr, (const double*)(sc + RR),
                          sc + SCL);
       DG_TRY(S.red_final(sc + RR));
@@ -777,10 +789,10 @@ int solve_poisson_ws(const dg_mesh* m, const dg_solve_params* sp, const double* 
 // Batched solves (the serving path): the solves of many meshes advance in
 // lockstep, one outer iteration at a time, and every step of an iteration
 // (operator applications, smoothing, transfers, vector updates, reductions)
-// is one launch over all meshes of the batch (per degree group), driven by
-// descriptor tables (batch.h) that stay in device memory while the set of
-// unconverged meshes is unchanged.  Each mesh runs the same arithmetic as
-// it would in a batch of one: its results do not depend on the others.
+// is one launch over the meshes of the batch (per degree group, up to a
+// few per launch, batch.h), with the meshes' descriptors in the kernel
+// arguments.  Each mesh runs the same arithmetic as in a batch of one: its
+// results do not depend on the others.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -809,20 +821,23 @@ constexpr bool vop_reduces(int op) {
 }
 
 // Workgroups per mesh: reductions use a block count that depends on the
-// vector length only (deterministic partials), one block for the finals.
+// vector length only (deterministic partials), one block for the finals;
+// small vectors get about one entry per thread (latency-bound sizes).
 int64_t vop_blocks(int op, int64_t n) {
   if (op == V_FINAL || op == V_GATHER) return 1;
-  if (vop_reduces(op)) return std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 256));
-  return std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 1024));
+  if (vop_reduces(op)) return red_blocks(n);
+  return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
 }
 
 // i0..i3: scalar slots of the operation (see the cases).
+constexpr int kVSegs = 16;  // segments per launch of a vector operation
+
 template <int OP>
-__global__ __launch_bounds__(kRedThreads) void k_vop(const VSeg* __restrict__ segs, int nseg, int i0, int i1, int i2,
-                                                     int i3, double* __restrict__ gather) {
+__global__ __launch_bounds__(kRedThreads) void k_vop(const SegArr<VSeg, kVSegs> segs, int i0, int i1, int i2, int i3,
+                                                     double* __restrict__ gather) {
   __shared__ double sh[kRedThreads / 64];
-  const int si = find_seg(segs, nseg, (int64_t)blockIdx.x);
-  const VSeg S = segs[si];
+  const int si = find_seg(segs, (int64_t)blockIdx.x);
+  const VSeg S = segs.s[si];
   const int64_t lb = (int64_t)blockIdx.x - S.blk0;
   const int64_t n = S.n, st = S.nblk * (int64_t)blockDim.x;
   const int64_t i00 = lb * (int64_t)blockDim.x + threadIdx.x;
@@ -1006,20 +1021,11 @@ struct BInst {
   double seconds = 0;
 };
 
-// Descriptor bytes and the launches that use them.
+// The launches of one phase of an outer iteration, with their descriptors.
 struct Prog {
-  std::vector<char> tab;
-  std::vector<std::function<int(const char*, hipStream_t)>> steps;
+  std::vector<std::function<int(hipStream_t)>> steps;
   std::vector<BInst*> who;   // meshes whose applies are counted
   std::vector<int> a64, a32;  // level-0 operator applications per run, per entry of who
-  const char* dev = nullptr;
-  int epoch = -1;
-  int64_t put_bytes(const void* p, size_t bytes) {
-    const size_t off = (tab.size() + 255) & ~size_t(255);
-    tab.resize(off + bytes);
-    std::memcpy(tab.data() + off, p, bytes);
-    return (int64_t)off;
-  }
   void count(BInst* in, bool f64) {
     for (size_t k = 0; k < who.size(); ++k)
       if (who[k] == in) {
@@ -1034,8 +1040,8 @@ struct Prog {
 
 using Set = std::vector<BInst*>;
 
-// Host staging for the descriptor uploads and the scalar read-backs: pinned
-// memory per host thread, kept for the thread's lifetime and grown on demand.
+// Pinned host rows for the scalar read-backs, per host thread, kept for the
+// thread's lifetime and grown on demand.
 struct Pinned {
   char* p = nullptr;
   size_t cap = 0;
@@ -1048,13 +1054,15 @@ int pinned_get(size_t bytes, char** out, hipEvent_t* ev) {
   if (!P.ev && hipEventCreateWithFlags(&P.ev, hipEventDisableTiming) != hipSuccess)
     return set_error(DG_ERR_HIP, "event creation failed");
   if (P.cap < bytes) {
+    // grow geometrically: reallocating pinned memory is slow and may wait for the device
+    const size_t want = std::max({bytes, 2 * P.cap, size_t(1) << 20});
     if (P.p) (void)hipHostFree(P.p);
     P.p = nullptr;
     P.cap = 0;
     void* q = nullptr;
-    if (int rc = check_hip(hipHostMalloc(&q, bytes, hipHostMallocDefault), "pinned staging")) return rc;
+    if (int rc = check_hip(hipHostMalloc(&q, want, hipHostMallocDefault), "pinned read-back rows")) return rc;
     P.p = static_cast<char*>(q);
-    P.cap = bytes;
+    P.cap = want;
   }
   *out = P.p;
   *ev = P.ev;
@@ -1067,41 +1075,14 @@ class Batch {
   const dg_solve_params* sp = nullptr;
   hipStream_t s = nullptr;
   double* gather = nullptr;   // device: kGatherRow doubles per mesh
-  char* arena = nullptr;      // device descriptor arena
-  size_t arena_cap = 0, top = 0;
-  int epoch = 0;
-  char* stage = nullptr;      // pinned: same offsets as the arena, then the read-back rows
-  double* rb = nullptr;
+  double* rb = nullptr;       // pinned host copy of the gather rows
   hipEvent_t ev = nullptr;
   bool mixed = false;
   int deg0 = 1, degc = 1;
 
-  // ---- upload and run ----
-  int upload(Prog& P) {
-    if (P.epoch == epoch) return DG_OK;
-    const size_t need = (P.tab.size() + 255) & ~size_t(255);
-    if (need > arena_cap) return set_error(DG_ERR_WORKSPACE, "batched solve: descriptor workspace too small");
-    if (top + need > arena_cap) {
-      // every launch that reads the arena (and every copy from the staging
-      // area) has run once the stream is idle
-      if (int rc = check_hip(hipStreamSynchronize(s), "descriptor arena reuse")) return rc;
-      top = 0;
-      ++epoch;
-    }
-    std::memcpy(stage + top, P.tab.data(), P.tab.size());
-    if (int rc = check_hip(hipMemcpyAsync(arena + top, stage + top, P.tab.size(), hipMemcpyHostToDevice, s),
-                           "descriptor upload"))
-      return rc;
-    P.dev = arena + top;
-    P.epoch = epoch;
-    top += need;
-    return DG_OK;
-  }
   int run(Prog& P) {
-    if (P.steps.empty()) return DG_OK;
-    if (int rc = upload(P)) return rc;
     for (auto& f : P.steps)
-      if (int rc = f(P.dev, s)) return rc;
+      if (int rc = f(s)) return rc;
     for (size_t k = 0; k < P.who.size(); ++k) {
       P.who[k]->applies64 += P.a64[k];
       P.who[k]->applies32 += P.a32[k];
@@ -1122,31 +1103,38 @@ class Batch {
   void vop(Prog& P, const Set& set, const std::function<void(VSeg&, BInst&)>& fill, int i0 = -1, int i1 = -1,
            int i2 = -1, int i3 = -1) {
     std::vector<VSeg> v;
-    int64_t blk = 0;
     for (BInst* in : set) {
       VSeg g{};
       g.sc = in->S.sc;
       g.part = in->S.part;
       fill(g, *in);
-      g.blk0 = blk;
       g.nblk = vop_blocks(OP, g.n);
-      blk += g.nblk;
       v.push_back(g);
     }
     if (v.empty()) return;
-    const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(VSeg));
-    const int nseg = (int)v.size();
     double* ga = gather;
-    P.steps.push_back([=](const char* base, hipStream_t st) {
-      hipLaunchKernelGGL((k_vop<OP>), dim3((unsigned)blk), dim3(kRedThreads), 0, st,
-                         reinterpret_cast<const VSeg*>(base + off), nseg, i0, i1, i2, i3, ga);
-      return check_hip(hipGetLastError(), "batched vector launch");
+    P.steps.push_back([v, i0, i1, i2, i3, ga](hipStream_t st) -> int {
+      for (size_t c0 = 0; c0 < v.size(); c0 += kVSegs) {
+        SegArr<VSeg, kVSegs> a{};
+        a.n = (int)std::min<size_t>(kVSegs, v.size() - c0);
+        int64_t blk = 0;
+        for (int i = 0; i < a.n; ++i) {
+          a.s[i] = v[c0 + i];
+          a.s[i].blk0 = blk;
+          blk += a.s[i].nblk;
+        }
+        hipLaunchKernelGGL((k_vop<OP>), dim3((unsigned)blk), dim3(kRedThreads), 0, st, a, i0, i1, i2, i3, ga);
+        if (int rc = check_hip(hipGetLastError(), "batched vector launch")) return rc;
+      }
+      return DG_OK;
     });
   }
-  // sc[o1] (and sc[o2]) = the reduction just built into the partials (n entries each)
+  // sc[o1] (and sc[o2]) = the reduction just built into the partials (n
+  // entries each); i0: the scalar slot the reduction's own pass reads
   template <int OP>
-  void reduce(Prog& P, const Set& set, const std::function<void(VSeg&, BInst&)>& fill, int o1, int o2 = -1) {
-    vop<OP>(P, set, fill);
+  void reduce(Prog& P, const Set& set, const std::function<void(VSeg&, BInst&)>& fill, int o1, int o2 = -1,
+              int i0 = -1) {
+    vop<OP>(P, set, fill, i0);
     vop<V_FINAL>(P, set, [&](VSeg& g, BInst& in) {
       VSeg t{};
       fill(t, in);
@@ -1165,8 +1153,6 @@ class Batch {
       if (std::find(nps.begin(), nps.end(), in->m->np_p) == nps.end()) nps.push_back(in->m->np_p);
     for (int np : nps) {
       std::vector<PoiSeg<T>> v;
-      int64_t blk = 0;
-      const int cb = poisson_cells_per_block(np);
       for (BInst* in : set) {
         if (in->m->np_p != np) continue;
         PoiSeg<T> g{};
@@ -1174,15 +1160,11 @@ class Batch {
         g.ncell = l > 0 ? in->m->mg[l].ncell : in->m->ncell;
         fill(g, *in);
         g.E.kind = kind;
-        g.blk0 = blk;
-        blk += (g.ncell + cb - 1) / cb;
         v.push_back(g);
         if (l == 0) P.count(in, sizeof(T) == 8);
       }
-      const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(PoiSeg<T>));
-      const int nseg = (int)v.size();
-      P.steps.push_back([=](const char* base, hipStream_t st) {
-        return launch_poisson_batched<T>(np, kind, reinterpret_cast<const PoiSeg<T>*>(base + off), nseg, blk, st);
+      P.steps.push_back([v, np, kind](hipStream_t st) {
+        return launch_poisson_batched<T>(np, kind, v.data(), (int)v.size(), st);
       });
     }
   }
@@ -1195,50 +1177,35 @@ class Batch {
     }
     for (const auto& gr : groups) {
       std::vector<TrSeg<T>> v;
-      int64_t blk = 0;
-      const int cpc = mg_cells_per_block(gr.first, gr.second);
       for (BInst* in : set) {
         if (in->m->np_p != gr.first || mg_full_transfer(in->m, l) != gr.second) continue;
         TrSeg<T> g{};
         g.tr = mg_transfer_geometry(in->m, l);
         g.ncc = in->m->mg[l + 1].ncell;
         fill(g, *in);
-        g.blk0 = blk;
-        blk += (g.ncc + cpc - 1) / cpc;
         v.push_back(g);
       }
-      const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(TrSeg<T>));
-      const int nseg = (int)v.size();
       const int np = gr.first;
       const bool full = gr.second;
-      P.steps.push_back([=](const char* base, hipStream_t st) {
-        const TrSeg<T>* d = reinterpret_cast<const TrSeg<T>*>(base + off);
-        return restrict_ ? launch_mg_restrict_batched<T>(np, full, d, nseg, blk, st)
-                         : launch_mg_prolong_batched<T>(np, full, d, nseg, blk, st);
+      P.steps.push_back([v, np, full, restrict_](hipStream_t st) {
+        return restrict_ ? launch_mg_restrict_batched<T>(np, full, v.data(), (int)v.size(), st)
+                         : launch_mg_prolong_batched<T>(np, full, v.data(), (int)v.size(), st);
       });
     }
   }
   template <typename T>
   void dense(Prog& P, const Set& set, int l, const std::function<void(DenseSeg<T>&, BInst&)>& fill) {
     std::vector<DenseSeg<T>> v;
-    int64_t blk = 0;
-    const int rpb = dense_rows_per_block();
     for (BInst* in : set) {
       DenseSeg<T> g{};
       g.n = in->m->mg[l].n;
       g.B = reinterpret_cast<const T*>(sizeof(T) == 8 ? (const void*)in->m->coarse_inv
                                                       : (const void*)in->m->coarse_inv32);
       fill(g, *in);
-      g.blk0 = blk;
-      blk += (g.n + rpb - 1) / rpb;
       v.push_back(g);
     }
     if (v.empty()) return;
-    const int64_t off = P.put_bytes(v.data(), v.size() * sizeof(DenseSeg<T>));
-    const int nseg = (int)v.size();
-    P.steps.push_back([=](const char* base, hipStream_t st) {
-      return launch_dense_batched<T>(reinterpret_cast<const DenseSeg<T>*>(base + off), nseg, blk, st);
-    });
+    P.steps.push_back([v](hipStream_t st) { return launch_dense_batched<T>(v.data(), (int)v.size(), st); });
   }
 
   // ---- multigrid V-cycle in lockstep ----
@@ -1397,7 +1364,7 @@ class Batch {
         g.a = in.S.x32;
         g.b = in.S.r;
         g.c = zo(in);
-      }, rz, zoldsel >= 0 ? rzx : -1);
+      }, rz, zoldsel >= 0 ? rzx : -1, B_SCL);
       return;
     }
     vcycle<double>(P, set, 0, [zb](BInst& in, int w) {
@@ -1533,27 +1500,6 @@ int lanczos_lmax(const double* h, double* out) {
 
 size_t batch_gather_bytes(int n) { return up256(sizeof(double) * kGatherRow * (size_t)n); }
 
-// Descriptor bytes: the largest program (the V-cycle) with every level
-// smoothed by the longest polynomial, room for the six programs of an
-// outer iteration (two V-cycles among them) and the occasional residual
-// replacement, plus slack.
-size_t batch_arena_bytes(const dg_mesh* const* meshes, int n, const dg_solve_params* sp) {
-  const int d0 = std::max(1, sp->cheb_degree);
-  const int dc = sp->coarse_degree > 0 ? sp->coarse_degree : d0;
-  const size_t per_level = (size_t)(2 * std::max(d0, dc) + 4 * d0 + 8);
-  const size_t seg = std::max({sizeof(PoiSeg<double>), sizeof(TrSeg<double>), sizeof(VSeg)});
-  size_t segs = 0, levels = 0;
-  for (int i = 0; i < n; ++i) {
-    const int L = std::max(1, meshes[i]->mg_nlev);
-    segs += per_level * L + 64;
-    levels = std::max<size_t>(levels, (size_t)L);
-  }
-  // every launch aligns its table to 256 bytes; a V-cycle has at most
-  // ~per_level launches per level and degree group (5 groups)
-  const size_t launches = 5 * (per_level * levels + 64);
-  return up256(4 * (segs * seg + launches * 256) + (1 << 20));
-}
-
 int solve_batched(const dg_mesh* const* meshes, int n, const dg_solve_params* sp, const double* const* b,
                   double* const* x, void* const* ws, const size_t* ws_bytes, dg_solve_stats* stats, int32_t* codes,
                   void* bws, size_t bws_bytes, hipStream_t s) {
@@ -1573,8 +1519,7 @@ int solve_batched(const dg_mesh* const* meshes, int n, const dg_solve_params* sp
     if (b[i] == x[i]) return set_error(DG_ERR_ARG, "b and x must not alias");
   }
   const size_t gb = batch_gather_bytes(n);
-  const size_t ab = batch_arena_bytes(meshes, n, sp);
-  if (bws_bytes < gb + ab) return set_error(DG_ERR_WORKSPACE, "batched solve: descriptor workspace too small");
+  if (bws_bytes < gb) return set_error(DG_ERR_WORKSPACE, "batched solve: workspace too small");
   Batch B;
   B.sp = sp;
   B.s = s;
@@ -1582,12 +1527,9 @@ int solve_batched(const dg_mesh* const* meshes, int n, const dg_solve_params* sp
   B.deg0 = sp->cheb_degree;
   B.degc = sp->coarse_degree > 0 ? sp->coarse_degree : sp->cheb_degree;
   B.gather = static_cast<double*>(bws);
-  B.arena = static_cast<char*>(bws) + gb;
-  B.arena_cap = ab;
   char* pin = nullptr;
-  if (int rc = pinned_get(ab + gb, &pin, &B.ev)) return rc;
-  B.stage = pin;
-  B.rb = reinterpret_cast<double*>(pin + ab);
+  if (int rc = pinned_get(gb, &pin, &B.ev)) return rc;
+  B.rb = reinterpret_cast<double*>(pin);
   B.I.resize(n);
   Set all;
   for (int i = 0; i < n; ++i) {
@@ -1877,7 +1819,7 @@ int64_t dg_solve_batch_workspace_bytes(const dg_mesh* const* meshes, int32_t n, 
     return set_error(DG_ERR_ARG, "batched solve: NULL argument or batch size outside [1, DG_MAX_BATCH]");
   for (int i = 0; i < n; ++i)
     if (!meshes[i]) return set_error(DG_ERR_ARG, "batched solve: NULL mesh");
-  return (int64_t)(batch_gather_bytes(n) + batch_arena_bytes(meshes, n, sp));
+  return (int64_t)batch_gather_bytes(n);
 }
 
 int dg_solve_poisson_batched(const dg_mesh* const* meshes, int32_t n, const dg_solve_params* sp,

@@ -8,9 +8,13 @@ device-memory footprint fits the budget, keeps every admitted instance's mesh
 tables and vectors resident on the device, and advances all instances that
 are in their velocity phase together: one batched library call per round
 covers every such instance (one launch per degree group and cell class).
-Solves run concurrently on worker threads, each on its own HIP stream, so
-they overlap with each other and with the batched velocity rounds; the
-library calls release the interpreter lock.  A request whose setup or solve
+The instances of one mesh shape that finish their velocity phase in the
+same round solve together: one batched solve call advances all of their
+pressure solves in lockstep (one launch per iteration step, a mesh leaving
+the batch when it converges; the call returns with its slowest mesh, so
+only like meshes share a call).  Solve batches run on worker threads, each on
+its own HIP stream, so they overlap with each other and with the batched
+velocity rounds; the library calls release the interpreter lock.  A request whose setup or solve
 fails is marked failed and its resources are released; the others go on.
 
 Latency is completion minus scheduled arrival on the host monotonic clock.
@@ -28,7 +32,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Mesh, _lib, apply_velocity_residual_batched, batch_workspace
+from . import Mesh, _lib, apply_velocity_residual_batched, batch_workspace, solve_poisson_batched
 from .inputs import Request, ServingConfig, draw_inputs, serving_requests
 
 
@@ -115,10 +119,12 @@ class Server:
     slots: most instances admitted at once.
     workers: threads (and HIP streams) for setup and solves.
     keep_results: keep each request's final r and x (device tensors).
+    batch_solves: solve the instances that finish their velocity phase in
+        the same round in one batched call (else one solve call each).
     """
 
     def __init__(self, budget_bytes=32 << 30, slots=64, workers=8, applies=10, solve_kw=None,
-                 keep_results=False, device=None):
+                 keep_results=False, device=None, batch_solves=True):
         import torch
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -131,6 +137,7 @@ class Server:
         kw.update(solve_kw or {})
         self.solve_kw = kw
         self.keep = keep_results
+        self.batch_solves = bool(batch_solves)
         self._tls = threading.local()
         self.main = torch.cuda.Stream(device=self.device)
         self.batch_ws = batch_workspace(self.slots, self.device)
@@ -163,17 +170,53 @@ class Server:
             inst.stream.synchronize()
         return inst
 
-    def _solve(self, inst: _Instance):
+    def _batch_ws(self, meshes, sp):
+        """The calling worker's descriptor workspace for a batched solve,
+        kept between calls and grown (doubling) when a batch needs more."""
+        need = int(_lib.check(_lib.lib().dg_solve_batch_workspace_bytes(
+            (ctypes.c_void_p * len(meshes))(*[m.handle.value for m in meshes]), len(meshes), ctypes.byref(sp))))
+        ws = getattr(self._tls, "bws", None)
+        if ws is None or ws.numel() < need:
+            size = max(need, 2 * ws.numel() if ws is not None else 0, 8 << 20)
+            ws = self._tls.bws = self.torch.empty(size, dtype=self.torch.uint8, device=self.device)
+        return ws
+
+    def _solve(self, insts):
+        """Solve the instances' pressure problems (one batched call, or one
+        call each); returns [(inst, stats or None, error or None)]."""
         torch = self.torch
-        inst.stream = self._stream()
-        with torch.cuda.device(self.device), torch.cuda.stream(inst.stream):
-            inst.stream.wait_event(inst.event)        # velocity rounds of this instance are done
+        stream = self._stream()
+        out = []
+        with torch.cuda.device(self.device), torch.cuda.stream(stream):
+            for inst in insts:
+                inst.stream = stream
+                stream.wait_event(inst.event)         # velocity rounds of this instance are done
             try:
-                _, st = inst.mesh.solve_poisson(inst.b, inst.x, sp=self._sp(), workspace=inst.ws,
-                                                stream=inst.stream)
+                sp = self._sp()
+                # the batched solve needs a coarser multigrid level on every mesh; a lone
+                # mesh takes the single call, whose result is bit for bit the same
+                batch = [i for i in insts if self.batch_solves and sp.multigrid and len(i.mesh.mg_levels()) >= 2]
+                if len(batch) < 2:
+                    batch = []
+                if batch:
+                    meshes = [i.mesh for i in batch]
+                    bws = self._batch_ws(meshes, sp)
+                    _, stats, codes = solve_poisson_batched(meshes, [i.b for i in batch], [i.x for i in batch],
+                                                            sp=sp, workspaces=[i.ws for i in batch], batch_ws=bws,
+                                                            stream=stream)
+                    for inst, st, code in zip(batch, stats, codes):
+                        out.append((inst, st, None if code == 0 else _lib.DgError(code, f"solve status {code}")))
+                for inst in insts:
+                    if inst in batch:
+                        continue
+                    try:
+                        _, st = inst.mesh.solve_poisson(inst.b, inst.x, sp=sp, workspace=inst.ws, stream=stream)
+                        out.append((inst, st, None))
+                    except Exception as e:  # noqa: BLE001 (recorded per request)
+                        out.append((inst, None, e))
             finally:
-                inst.stream.synchronize()
-        return inst, st
+                stream.synchronize()
+        return out
 
     # -- main loop ---------------------------------------------------------
     def run(self, requests, time_scale=1.0) -> ServeReport:
@@ -231,16 +274,24 @@ class Server:
                                                         [i.r for i in active_apply], workspace=self.batch_ws,
                                                         stream=self.main)
                     rounds += 1
-                    still = []
+                    still, ready = [], []
                     for inst in active_apply:
                         inst.applies_done += 1
                         if inst.applies_done >= self.applies:
                             inst.event = torch.cuda.Event()
                             inst.event.record(self.main)
-                            futures[pool.submit(self._solve, inst)] = ("solve", inst)
+                            ready.append(inst)
                         else:
                             still.append(inst)
                     active_apply = still
+                    # one solve batch per mesh shape: a batch returns when its slowest
+                    # mesh converges, so only like meshes wait for each other
+                    groups = {}
+                    for inst in ready:
+                        m = inst.req.workload.mesh
+                        groups.setdefault((m.nx, m.ny, m.nz, m.k_p), []).append(inst)
+                    for grp in groups.values():
+                        futures[pool.submit(self._solve, grp)] = ("solve", grp)
 
                 # collect finished jobs; block only when nothing else can progress
                 if futures:
@@ -265,24 +316,26 @@ class Server:
                             else:
                                 inst.event = torch.cuda.Event()
                                 inst.event.record(self.main)
-                                futures[pool.submit(self._solve, inst)] = ("solve", inst)
+                                futures[pool.submit(self._solve, [inst])] = ("solve", [inst])
                         else:
-                            o = inst.out
-                            o.done = time.monotonic() - t0
-                            o.latency = o.done - o.arrival
-                            o.applies = inst.applies_done
-                            if err is not None:
-                                o.ok = False
-                                o.error = f"solve: {err}"
-                            else:
-                                st = f.result()[1]
-                                o.poisson_applies = st.op_applies_f64 + st.op_applies_f32
-                                o.outer_its = st.outer_its
-                                o.rel_resid = st.rel_resid
-                                if self.keep:
-                                    o.r, o.x = inst.r, inst.x
-                            outcomes[inst.req.rid] = o
-                            release(inst)
+                            done_at = time.monotonic() - t0
+                            results = f.result() if err is None else [(i, None, err) for i in inst]
+                            for one, st, e in results:
+                                o = one.out
+                                o.done = done_at
+                                o.latency = o.done - o.arrival
+                                o.applies = one.applies_done
+                                if e is not None:
+                                    o.ok = False
+                                    o.error = f"solve: {e}"
+                                else:
+                                    o.poisson_applies = st.op_applies_f64 + st.op_applies_f32
+                                    o.outer_its = st.outer_its
+                                    o.rel_resid = st.rel_resid
+                                    if self.keep:
+                                        o.r, o.x = one.r, one.x
+                                outcomes[one.req.rid] = o
+                                release(one)
                 elif pending and not active_apply:
                     delay = pending[0].arrival * time_scale - (time.monotonic() - t0)
                     if delay > 0:
