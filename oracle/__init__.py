@@ -63,6 +63,7 @@ def lib():
         L.orc_num_enriched.argtypes = [P]
         L.orc_num_enriched.restype = ctypes.c_int64
         L.orc_velocity_residual.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
+        L.orc_convective_residual.argtypes = [P, _D, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
         L.orc_poisson_apply.argtypes = [P, _D, _I64, ctypes.c_int64, _D, ctypes.c_int]
         L.orc_poisson_diag.argtypes = [P, _I64, ctypes.c_int64, _D]
         L.orc_psi_point.argtypes = [P, _D, ctypes.c_int64, _D, _D]
@@ -188,6 +189,26 @@ def velocity_residual(cfg, u, tau, cells=None, absmode=False):
                                      cells.size, _ptr(r), int(absmode))
     if rc:
         raise RuntimeError(f"orc_velocity_residual failed: {rc}")
+    return r
+
+
+def convective_residual(cfg, u, tau, cells=None, absmode=False):
+    """Convective form F^c_e (Sec. 4.2, eq. convstepspat): the velocity
+    residual's convective volume and face terms alone (viscous terms, which
+    all carry nu, dropped; psi keeps the physical nu).  Layout as
+    velocity_residual."""
+    p = params(cfg)
+    u = _f64(u)
+    n = num_dofs(cfg, 0)
+    if u.size != n:
+        raise ValueError(f"u has {u.size} entries, expected {n}")
+    tau = _f64(tau) if tau is not None else np.zeros(1)
+    cells = _cells(cfg, cells)
+    r = np.zeros(n)
+    rc = lib().orc_convective_residual(ctypes.byref(p), _ptr(u), _ptr(tau), cells.ctypes.data_as(_I64),
+                                       cells.size, _ptr(r), int(absmode))
+    if rc:
+        raise RuntimeError(f"orc_convective_residual failed: {rc}")
     return r
 
 

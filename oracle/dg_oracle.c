@@ -230,6 +230,7 @@ typedef struct {
   const double *tau;  /* wall shear stress per wall-face quadrature point */
   const double *tau_nodes; /* or: nodal wall shear stress [wall][nz][nx] (Sec. 3.2, m = 1) */
   signed char *act;   /* per enriched cell: 1 enrichment on, 0 off; NULL: all on */
+  int conv_only;      /* velocity residual: 1 keeps the convective terms alone */
 } ctx;
 
 /* Wall-normal vertex coordinate, Sec. 5.1: f(t) = tanh(gamma(2t-1))/tanh(gamma). */
@@ -650,7 +651,9 @@ int64_t orc_num_enriched(const orc_params *P) {
 static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int absmode,
                      double *bv, double (*bg)[3], double *bv2, double (*bg2)[3]) {
   int n = C->npu, np3 = n * n * n;
-  double nu = C->P.nu, theta = C->P.theta;
+  /* every viscous term carries nu; the convective form F^c drops them (psi
+   * keeps the physical nu through y+) */
+  double nu = C->conv_only ? 0.0 : C->P.nu, theta = C->P.theta;
   double *re = r + (int64_t)e * 3 * np3;
   double rt[3] = {0, 0, 0};
   for (int i = 0; i < 3 * np3; ++i) re[i] = 0.0;
@@ -788,10 +791,11 @@ static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int ab
 }
 
 static int velocity_residual(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
-                             const int64_t *cells, int64_t ncells, double *r, int absmode) {
+                             const int64_t *cells, int64_t ncells, double *r, int absmode, int conv_only) {
   ctx C;
   if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
+  C.conv_only = conv_only;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
   int n = C.npu, np3 = n * n * n;
@@ -815,12 +819,20 @@ static int velocity_residual(const orc_params *P, const double *u, const double 
 
 int orc_velocity_residual(const orc_params *P, const double *u, const double *tau_w,
                           const int64_t *cells, int64_t ncells, double *r, int absmode) {
-  return velocity_residual(P, u, tau_w, NULL, cells, ncells, r, absmode);
+  return velocity_residual(P, u, tau_w, NULL, cells, ncells, r, absmode, 0);
 }
 
 int orc_velocity_residual_nodal(const orc_params *P, const double *u, const double *tau_nodes,
                                 const int64_t *cells, int64_t ncells, double *r, int absmode) {
-  return velocity_residual(P, u, NULL, tau_nodes, cells, ncells, r, absmode);
+  return velocity_residual(P, u, NULL, tau_nodes, cells, ncells, r, absmode, 0);
+}
+
+/* Convective form F^c_e of the explicit step (Sec. 4.1 eq. convstep, Sec. 4.2
+ * eq. convstepspat): the residual's volume flux -u (x) u and face flux
+ * {{u (x) u}} n + Lambda/2 (u- - u+), without the viscous terms. */
+int orc_convective_residual(const orc_params *P, const double *u, const double *tau_w,
+                            const int64_t *cells, int64_t ncells, double *r, int absmode) {
+  return velocity_residual(P, u, tau_w, NULL, cells, ncells, r, absmode, 1);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -166,6 +166,37 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     return (x, conds) if return_cond else x
 
 
+def mass_apply(cfg, x, psi):
+    """y = M x with the velocity mass matrix of every cell (the forward
+    operator that inverse_mass inverts; same blocks, same psi convention:
+    zero rows switch a cell's enrichment off, its unknowns then map to 0)."""
+    if cfg.wall_amp != 0.0:
+        raise ValueError("flat meshes only")
+    n3 = (cfg.k_u + 1) ** 3
+    x = np.asarray(x, dtype=np.float64)
+    y = np.zeros_like(x)
+    eta = vertex_eta(cfg)
+    off = cfg.ncell * 3 * n3
+    enr = {int(e): k for k, e in enumerate(enriched_cells(cfg))}
+    pts_e, wts_e = volume_rule(cfg)
+    V_e = basis_at(cfg, pts_e)
+    pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
+    V_r = basis_at(cfg, pts_r)
+    M_reg = V_r.T @ (wts_r[:, None] * V_r)
+    for e in range(cfg.ncell):
+        k = enr.get(e)
+        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e)
+        for c in range(3):
+            xp = x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
+            if k is not None and M.shape[0] == n3 + 1:
+                v = M @ np.concatenate([xp, [x[off + 3 * k + c]]])
+                y[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = v[:n3]
+                y[off + 3 * k + c] = v[n3]
+            else:
+                y[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = M @ xp
+    return y
+
+
 def _mass_block(cfg, e, psi_k, eta, M_reg, V_e, wts_e):
     """Per-component mass matrix of cell e over its local basis (N_B, plus psi
     while an enriched cell's enrichment is on), the cell's own rule."""

@@ -215,3 +215,34 @@ def test_enriched_viscous_symmetry():
 
     a, b = w @ lin(v), v @ lin(w)
     assert abs(a - b) < 1e-11 * abs(a)
+
+
+@pytest.mark.parametrize("cfg", VISC_CFGS)
+def test_convective_form_is_residual_minus_dense_viscous(cfg):
+    """F^c (Sec. 4.2, eq. convstepspat) = r - V with V the independent dense
+    face-by-face viscous assembly, and F^c is homogeneous of degree 2."""
+    rng = np.random.default_rng(15)
+    u = rng.uniform(-1, 1, cfg.n_vel)
+    c = O.convective_residual(cfg, u, None)
+    r = O.velocity_residual(cfg, u, None)
+    A = dense.viscous_matrix(cfg)
+    assert rel(r - c, A @ u) < 1e-12
+    assert rel(O.convective_residual(cfg, 3 * u, None), 9 * c) < 1e-13
+
+
+def test_convective_form_with_enrichment():
+    """With walls and the enrichment: r - F^c is linear in u and F^c is
+    positively homogeneous of degree 2 (every convective term is quadratic;
+    Lambda carries absolute values, so the scale factor is positive; every
+    viscous term is linear)."""
+    wl = PRESETS["tiny"]
+    cfg = wl.mesh
+    inp = draw_inputs(wl)
+    u = inp["u"]
+    c1 = O.convective_residual(cfg, u, inp["tau"])
+    c2 = O.convective_residual(cfg, 2 * u, inp["tau"])
+    assert rel(c2, 4 * c1) < 1e-13
+    d1 = O.velocity_residual(cfg, u, inp["tau"]) - c1
+    d2 = O.velocity_residual(cfg, 2 * u, inp["tau"]) - c2
+    assert rel(d2, 2 * d1) < 1e-12
+    assert np.abs(c1).max() > 0 and np.abs(d1).max() > 0
