@@ -203,6 +203,16 @@ void dg_destroy_mesh(dg_mesh* mesh);
  *   u, r: device vectors of dg_num_dofs(mesh, 0) entries; u != r. */
 int dg_apply_velocity_residual(const dg_mesh* mesh, dg_prec prec, const void* u, void* r, void* stream);
 
+/* Convective part of the velocity residual, the term F^c_e of the explicit
+ * convective step (paper Sec. 4.1 eq. convstep, Sec. 4.2 eq. convstepspat):
+ *   r_c(phi) = -(grad phi, u (x) u)_e
+ *            + sum_F ( phi . [ {{u (x) u}} n + Lambda/2 (u- - u+) ] )_F,
+ * i.e. dg_apply_velocity_residual with nu = 0 (same kernels, local
+ * Lax-Friedrichs Lambda, mirror data u+ = -u- on no-slip walls, enriched
+ * cells u = u_bar + psi u~).  Arguments and errors as for
+ * dg_apply_velocity_residual. */
+int dg_apply_convective(const dg_mesh* mesh, dg_prec prec, const void* u, void* r, void* stream);
+
 /* Most meshes one batched call takes. */
 #define DG_MAX_BATCH 4096
 
@@ -364,6 +374,44 @@ int dg_eddy_viscosity(const dg_mesh* mesh, const double* u, double c_des, double
  *   u, out: device, dg_num_dofs(mesh, 0) doubles, distinct.  FP64, flat walls.
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
 int dg_apply_viscous_multiscale(const dg_mesh* mesh, const double* nut, const double* u, double* out, void* stream);
+
+/* Restarted GMRES parameters and statistics of the Helmholtz step. */
+typedef struct {
+  double rtol;          /* stop when ||gamma b - H x||_2 <= rtol ||gamma b||_2 (true residual, see below) */
+  int32_t max_iter;     /* cap on the Arnoldi steps over all restart cycles                           */
+  int32_t restart;      /* Krylov vectors per cycle, 1..100                                           */
+} dg_gmres_params;
+
+typedef struct {
+  int32_t iterations, restarts;
+  double rel_resid;     /* final ||gamma b - H x|| / ||gamma b||                                       */
+  double seconds;       /* host wall time of the call                                                  */
+} dg_gmres_stats;
+
+/* Device workspace of dg_solve_helmholtz: restart + 1 velocity vectors plus
+ * scalars, or a negative DG_ERR_* code. */
+int64_t dg_helmholtz_workspace_bytes(const dg_mesh* mesh, const dg_gmres_params* gp);
+
+/* Helmholtz step of the dual-splitting scheme (paper Sec. 4.1 eq. visc,
+ * Sec. 4.2 eq. helmholtzspat):
+ *   (gamma0/dt) M x + A x = (gamma0/dt) M b,
+ * A the multiscale viscous operator of dg_apply_viscous_multiscale with the
+ * eddy viscosity nut (adjoint sign -1, so A is not symmetric), M the
+ * velocity mass matrix, b the second intermediate velocity u_hathat.  Solved
+ * as H x = gamma x + M^{-1} A x = gamma b (gamma = gamma0/dt) by restarted
+ * GMRES in FP64 (the paper solves this step with GMRES, Sec. 5.1): the
+ * cell-wise M^{-1} of dg_apply_inverse_mass is the left preconditioner, and
+ * the residual is measured in that preconditioned form.  Modified
+ * Gram-Schmidt with the projections kept on the device, one host read-back
+ * per Arnoldi step, deterministic reductions; convergence is confirmed with
+ * the true residual.
+ *   nut: device, from dg_eddy_viscosity (may be NULL without enriched cells);
+ *   b, x: device, dg_num_dofs(mesh, 0) doubles, distinct; x holds the
+ *   initial guess (e.g. b); ws: >= dg_helmholtz_workspace_bytes.
+ *   Errors: DG_ERR_ARG, DG_ERR_WORKSPACE, DG_ERR_UNSUPPORTED (curved wall),
+ *   DG_ERR_NONFINITE, DG_ERR_NOT_CONVERGED (stats filled), DG_ERR_HIP. */
+int dg_solve_helmholtz(const dg_mesh* mesh, const double* nut, double gamma0_over_dt, const double* b, double* x,
+                       const dg_gmres_params* gp, void* ws, size_t ws_bytes, dg_gmres_stats* stats, void* stream);
 
 /* SIP Poisson operator y = A p, A = -L of paper Sec. 4.2 (pressure Laplace
  * term, flux eq. ipflux) with homogeneous Neumann data on the walls:

@@ -79,6 +79,17 @@ class Mesh:
         _lib.check(_lib.lib().dg_apply_velocity_residual(self.handle, prec, _dptr(u), _dptr(r), _stream_ptr(stream)))
         return r
 
+    def apply_convective(self, u, r=None, stream=None):
+        """dg_apply_convective: the convective part of the velocity residual."""
+        import torch
+        prec = self._check_vec(u, self.n_vel, "u")
+        if r is None:
+            r = torch.empty_like(u)
+        if self._check_vec(r, self.n_vel, "r") != prec:
+            raise ValueError("u and r must have the same dtype")
+        _lib.check(_lib.lib().dg_apply_convective(self.handle, prec, _dptr(u), _dptr(r), _stream_ptr(stream)))
+        return r
+
     def apply_poisson(self, p, y=None, stream=None):
         import torch
         prec = self._check_vec(p, self.n_p, "p")
@@ -281,6 +292,26 @@ class Mesh:
         out = torch.empty(max(self.n_enriched, 1), dtype=torch.int32, device=self.device)
         _lib.check(_lib.lib().dg_enrichment_active(self.handle, _dptr(out), _stream_ptr(stream)))
         return out[:self.n_enriched]
+
+    def solve_helmholtz(self, nut, gamma0_over_dt, b, x=None, rtol=1e-12, max_iter=500, restart=30, workspace=None,
+                        stream=None):
+        """dg_solve_helmholtz: (gamma0/dt) M x + A(nut) x = (gamma0/dt) M b by
+        restarted GMRES; returns (x, GmresStats)."""
+        import torch
+        self._check_f64(b, self.n_vel, "b")
+        if x is None:
+            x = b.clone()
+        self._check_f64(x, self.n_vel, "x")
+        gp = _lib.GmresParams(rtol=rtol, max_iter=max_iter, restart=restart)
+        if workspace is None:
+            nb = _lib.check(_lib.lib().dg_helmholtz_workspace_bytes(self.handle, ctypes.byref(gp)))
+            workspace = torch.empty(int(nb), dtype=torch.uint8, device=self.device)
+        st = _lib.GmresStats()
+        _lib.check(_lib.lib().dg_solve_helmholtz(self.handle, _dptr(nut) if nut is not None else None,
+                                                 float(gamma0_over_dt), _dptr(b), _dptr(x), ctypes.byref(gp),
+                                                 _dptr(workspace), workspace.numel(), ctypes.byref(st),
+                                                 _stream_ptr(stream)))
+        return x, st
 
     def solve_params(self, rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5,
                      multigrid=True, coarse_degree=3):

@@ -44,6 +44,15 @@ class SolveParams(ctypes.Structure):
                 ("multigrid", ctypes.c_int32), ("coarse_degree", ctypes.c_int32)]
 
 
+class GmresParams(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32)]
+
+
+class GmresStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_resid", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
 class SolveStats(ctypes.Structure):
     _fields_ = [("outer_its", ctypes.c_int32), ("inner_its_total", ctypes.c_int32),
                 ("op_applies_f64", ctypes.c_int32), ("op_applies_f32", ctypes.c_int32),
@@ -80,6 +89,10 @@ _SIGS = {
                                                           ctypes.c_size_t, _VP]),
     "dg_apply_poisson": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "dg_poisson_diagonal": (ctypes.c_int, [_VP, _VP, _VP]),
+    "dg_apply_convective": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "dg_helmholtz_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.POINTER(GmresParams)]),
+    "dg_solve_helmholtz": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, ctypes.POINTER(GmresParams), _VP,
+                                          ctypes.c_size_t, ctypes.POINTER(GmresStats), _VP]),
     "dg_mg_levels": (ctypes.c_int, [_VP, _VP, ctypes.c_int32]),
     "dg_mg_transfer": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP, _VP]),
     "dg_solve_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.POINTER(SolveParams)]),

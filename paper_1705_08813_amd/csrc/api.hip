@@ -527,6 +527,14 @@ int dg_apply_velocity_residual(const dg_mesh* m, dg_prec prec, const void* u, vo
   return launch_velocity(m, prec, u, r, static_cast<hipStream_t>(stream));
 }
 
+int dg_apply_convective(const dg_mesh* m, dg_prec prec, const void* u, void* r, void* stream) {
+  if (!m || !u || !r) return set_error(DG_ERR_ARG, "mesh/u/r is NULL");
+  if (prec != DG_F64 && prec != DG_F32) return set_error(DG_ERR_ARG, "unknown precision");
+  if (u == r) return set_error(DG_ERR_ARG, "u and r must not alias");
+  if (!aligned256(u) || !aligned256(r)) return set_error(DG_ERR_ARG, "u and r must be 256-byte aligned");
+  return launch_velocity(m, prec, u, r, static_cast<hipStream_t>(stream), true);
+}
+
 int64_t dg_batch_workspace_bytes(int32_t n) {
   if (n < 1 || n > DG_MAX_BATCH) return set_error(DG_ERR_ARG, "batch size must be in [1, DG_MAX_BATCH]");
   return batch_workspace_bytes(n);

@@ -222,7 +222,9 @@ int launch_dense_apply(int64_t n, dg_prec prec, const void* B, const void* b, vo
 size_t solve_bytes_mesh(const dg_mesh& m);
 // device data of the hierarchy (levels' heights and diagonals, coarse inverse)
 int mg_setup(dg_mesh* m, const std::vector<double>& eta0, double* coarse_scr, hipStream_t s);
-int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s);
+// convective_only: the residual with nu = 0 (its convective part alone)
+int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s,
+                    bool convective_only = false);
 // eddy viscosity nu_t at every point of the psi tables from the enrichment
 // coefficients of u, and out = A u for the multiscale viscous operator
 int launch_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double beta, double* nut, hipStream_t s);
@@ -244,6 +246,10 @@ int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* 
                            double* x, hipStream_t s);
 // x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)
 int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s);
+// Helmholtz step (helmholtz.hip): workspace bytes and the restarted GMRES solve
+int64_t helmholtz_workspace_bytes(const dg_mesh* m, int restart);
+int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const double* b, double* x, double rtol,
+                    int max_iter, int restart, void* ws, size_t ws_bytes, dg_gmres_stats* st, hipStream_t s);
 // u_new = L2 projection of u_old from the space of psi_prev onto that of psi
 int launch_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, hipStream_t s);
 // nodal wall shear stress [wall][nz][nx] of the FP64 velocity u (flat walls)

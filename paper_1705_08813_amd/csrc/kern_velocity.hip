@@ -1858,8 +1858,9 @@ int launch_viscous_multiscale(const dg_mesh* m, const double* nut, const double*
   return set_error(DG_ERR_UNSUPPORTED, "velocity degree/quadrature combination not compiled");
 }
 
-int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s) {
-  const MeshDev M = make_meshdev_u(m);
+int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipStream_t s, bool convective_only) {
+  MeshDev M = make_meshdev_u(m);
+  if (convective_only) M.nu = 0.0;  // every viscous term carries a factor nu
   const int np = m->np_u, nq = m->P.nq_u, nqw = m->P.nq_wn;
   // without enriched cells only the regular kernel runs: nq_wn is irrelevant
 #define X(a, b, c)                                                                 \

@@ -71,6 +71,23 @@ def test_velocity_residual_f64(name):
         assert _rel(re, oe) <= 1e-12, _rel(re, oe)
 
 
+@pytest.mark.parametrize("name", list(VEL_CASES))
+def test_convective_f64(name):
+    """dg_apply_convective against the oracle's convective form F^c (Sec. 4.2,
+    eq. convstepspat), polynomial and enrichment blocks at 1e-12."""
+    wl = VEL_CASES[name]
+    _log(f"[gpu] convective f64 case={name}")
+    inp = draw_inputs(wl)
+    c_orc = O.convective_residual(wl.mesh, inp["u"], inp["tau"])
+    mesh = Mesh(wl.mesh, inp["tau"])
+    c = mesh.apply_convective(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    cp, ce = _split(wl.mesh, c)
+    op, oe = _split(wl.mesh, c_orc)
+    assert _rel(cp, op) <= 1e-12, _rel(cp, op)
+    if oe.size:
+        assert _rel(ce, oe) <= 1e-12, _rel(ce, oe)
+
+
 @pytest.mark.parametrize("name", ["tiny", "k4_large_like", "k3_periodic", "curved_k3", "k5_curved_rule", "curved_k5",
                                   "curved_k4_stretched"])
 def test_velocity_residual_f32_bound(name):
