@@ -12,7 +12,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import enriched_cells, psi_volume, viscous_multiscale
+from . import (enriched_cells, enrichment_active, gauss, gauss_lobatto, lagrange, psi_point, psi_volume, psi_volume4,
+               vertex_eta, viscous_multiscale)
 from .project import inverse_mass, mass_apply
 
 
@@ -53,3 +54,119 @@ def helmholtz_residual(cfg, u_nut, tau, gamma, b, x):
     u_nut = np.zeros(cfg.n_vel) if u_nut is None else u_nut
     return gamma * mass_apply(cfg, x, psi) + viscous_multiscale(cfg, x, u_nut=u_nut, tau=tau) \
         - gamma * mass_apply(cfg, b, psi)
+
+
+# ---------------------------------------------------------------------------
+# Vorticity and the high-order pressure Neumann data (Sec. 4.1 eq. bc_d_pres;
+# Sec. 4.2 eq. ipflux on the walls)
+# ---------------------------------------------------------------------------
+
+def _cell_grads(cfg, u, e, pts, h, psi4_k, ut):
+    """Values (npts, 3) and gradients (npts, 3, 3) [q, component, direction]
+    of the velocity-space field u on cell e at reference points, psi u~
+    included when psi4_k (psi and grad psi at the points) is given."""
+    from .project import basis_at, _basis_grad_at
+    n3 = (cfg.k_u + 1) ** 3
+    U = np.asarray(u[e * 3 * n3:(e + 1) * 3 * n3], dtype=np.float64).reshape(3, n3)
+    V = basis_at(cfg, pts)
+    G = _basis_grad_at(cfg, pts, h)
+    val = V @ U.T
+    grad = np.einsum("qbd,cb->qcd", G, U)
+    if psi4_k is not None:
+        val += psi4_k[:, 0:1] * ut[None, :]
+        grad += ut[None, :, None] * psi4_k[:, None, 1:4]
+    return V, val, grad
+
+
+def _curl(grad):
+    return np.stack([grad[:, 2, 1] - grad[:, 1, 2], grad[:, 0, 2] - grad[:, 2, 0], grad[:, 1, 0] - grad[:, 0, 1]], 1)
+
+
+def vorticity_rhs(cfg, u, tau):
+    """b(v) = (v, curl u)_e for every velocity test function (N_B e_c, and
+    psi e_c in an enriched cell whose enrichment is on) with the cell's
+    velocity rule (nq_u^3, or nq_u x nq_wn x nq_u), u = u_bar + psi u~."""
+    from .project import volume_rule
+    n3 = (cfg.k_u + 1) ** 3
+    u = np.asarray(u, dtype=np.float64)
+    b = np.zeros(cfg.n_vel)
+    eta = vertex_eta(cfg)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    off = cfg.ncell * 3 * n3
+    ecells = enriched_cells(cfg)
+    enr = {int(e): k for k, e in enumerate(ecells)}
+    psi4 = psi_volume4(cfg, ecells, tau=tau) if ecells.size else None
+    pts_e, wts_e = volume_rule(cfg)
+    pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
+    for e in range(cfg.ncell):
+        ey = (e // cfg.nx) % cfg.ny
+        h = (hx, eta[ey + 1] - eta[ey], hz)
+        k = enr.get(e)
+        pts, wts = (pts_e, wts_e) if k is not None else (pts_r, wts_r)
+        p4 = psi4[k] if k is not None else None
+        ut = u[off + 3 * k:off + 3 * k + 3] if k is not None else None
+        V, _, grad = _cell_grads(cfg, u, e, pts, h, p4, ut)
+        cw = _curl(grad) * (wts * h[0] * h[1] * h[2])[:, None]
+        b[e * 3 * n3:(e + 1) * 3 * n3] = (V.T @ cw).T.reshape(-1)
+        if k is not None:
+            b[off + 3 * k:off + 3 * k + 3] = p4[:, 0] @ cw
+    return b
+
+
+def vorticity(cfg, u, tau):
+    """omega_h = L2 projection of curl u_h onto the enriched velocity space
+    (Sec. 4.2, below eq. ipflux): M omega = vorticity_rhs."""
+    return inverse_mass(cfg, vorticity_rhs(cfg, u, tau), _psi(cfg, tau))
+
+
+def pressure_neumann(cfg, us, omegas, betas, f, tau):
+    """Wall term of the pressure equation with the high-order Neumann data of
+    eq. bc_d_pres:  rhs(q) = int_wall q h_N dA,
+      h_N = -( sum_i beta_i (div F^c(u_i) + nu curl omega_i) - f ) . n,
+    div F^c(u) = div(u (x) u), n the outward normal (-e_y on the lower wall,
+    +e_y on the upper one), at the Gauss points of the velocity face rule
+    (nq_u x nq_u) against the pressure basis; u_i = u_bar + psi u~ and
+    omega_i likewise in enriched cells (psi = 0 on the wall, grad psi not)."""
+    if cfg.fully_periodic:
+        return np.zeros(cfg.n_p)
+    npu, npp = cfg.k_u + 1, cfg.k_p + 1
+    n3, p3 = npu ** 3, npp ** 3
+    off = cfg.ncell * 3 * n3
+    nodes_u, nodes_p = gauss_lobatto(npu), gauss_lobatto(npp)
+    gq, gw = gauss(cfg.nq_u)
+    eta = vertex_eta(cfg)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    enr = {int(e): k for k, e in enumerate(enriched_cells(cfg))}
+    act = enrichment_active(cfg, tau=tau) if enr else None
+    rhs = np.zeros(cfg.n_p)
+    for ey, s, sg in ((0, 0.0, -1.0), (cfg.ny - 1, 1.0, 1.0)):
+        for ez in range(cfg.nz):
+            for ex in range(cfg.nx):
+                e = ex + cfg.nx * (ey + cfg.ny * ez)
+                h = (hx, eta[ey + 1] - eta[ey], hz)
+                k = enr.get(e)
+                pts = np.array([(gq[a], s, gq[c]) for c in range(cfg.nq_u) for a in range(cfg.nq_u)])
+                wts = np.array([gw[a] * gw[c] * hx * hz for c in range(cfg.nq_u) for a in range(cfg.nq_u)])
+                p4 = None
+                if k is not None and act[k]:
+                    p4 = np.array([psi_point(cfg, tau, e, xi) for xi in pts])
+                hn = np.zeros(len(pts))
+                for u, om, beta in zip(us, omegas, betas):
+                    u = np.asarray(u, dtype=np.float64)
+                    om = np.asarray(om, dtype=np.float64)
+                    ut = u[off + 3 * k:off + 3 * k + 3] if p4 is not None else None
+                    ot = om[off + 3 * k:off + 3 * k + 3] if p4 is not None else None
+                    _, val, g = _cell_grads(cfg, u, e, pts, h, p4, ut)
+                    _, _, go = _cell_grads(cfg, om, e, pts, h, p4, ot)
+                    div = g[:, 0, 0] + g[:, 1, 1] + g[:, 2, 2]
+                    conv_y = np.einsum("qj,qj->q", g[:, 1, :], val) + val[:, 1] * div
+                    curl_y = go[:, 0, 2] - go[:, 2, 0]
+                    hn += beta * sg * (conv_y + cfg.nu * curl_y)
+                hn = -hn + sg * f[1]
+                for qi, xi in enumerate(pts):
+                    vx = lagrange(nodes_p, xi[0])[0]
+                    vy = lagrange(nodes_p, xi[1])[0]
+                    vz = lagrange(nodes_p, xi[2])[0]
+                    Np = np.einsum("m,j,i->mji", vz, vy, vx).reshape(-1)
+                    rhs[e * p3:(e + 1) * p3] += wts[qi] * hn[qi] * Np
+    return rhs

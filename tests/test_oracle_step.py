@@ -60,3 +60,125 @@ def test_helmholtz_solves_the_unscaled_equation(gamma):
     scale = gamma * np.abs(OP.mass_apply(cfg, b, psi)).max()
     assert np.abs(r).max() < 1e-10 * scale
     assert its > 1
+
+
+def _nodal(cfg, fun):
+    """Velocity-space coefficients of the nodal interpolant of fun(x, y, z)
+    -> (3,) (polynomial part; enrichment coefficients 0)."""
+    n = cfg.k_u + 1
+    n3 = n ** 3
+    gl = O.gauss_lobatto(n)
+    eta = O.vertex_eta(cfg)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    u = np.zeros(cfg.n_vel)
+    for e in range(cfg.ncell):
+        ex, ey, ez = e % cfg.nx, (e // cfg.nx) % cfg.ny, e // (cfg.nx * cfg.ny)
+        for m in range(n):
+            for j in range(n):
+                for i in range(n):
+                    X = (ex + gl[i]) * hx
+                    Y = eta[ey] + gl[j] * (eta[ey + 1] - eta[ey])
+                    Z = (ez + gl[m]) * hz
+                    v = fun(X, Y, Z)
+                    for c in range(3):
+                        u[(e * 3 + c) * n3 + i + n * (j + n * m)] = v[c]
+    return u
+
+
+def _field(X, Y, Z):
+    return np.array([Y * Y * Z - 0.3 * X, X * Z * Z + 0.5 * Y, X * X * Y - Z])
+
+
+def _curl_field(X, Y, Z):
+    # curl of _field: (d/dy u_z - d/dz u_y, d/dz u_x - d/dx u_z, d/dx u_y - d/dy u_x)
+    return np.array([X * X - 2 * X * Z, Y * Y - 2 * X * Y, Z * Z - 2 * Y * Z])
+
+
+@pytest.mark.parametrize("enriched", [False, True])
+def test_vorticity_exact_for_polynomial_fields(enriched):
+    """omega = L2 projection of curl u reproduces the curl of a degree-3
+    polynomial field exactly (its curl lies in the space); with the
+    enrichment in the space its coefficient vanishes."""
+    cfg = MeshConfig(nx=2, ny=3, nz=2, gamma=1.2, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3,
+                     enrich_lower=int(enriched), enrich_upper=int(enriched))
+    tau = np.full(cfg.n_tau, 1.0)
+    u = _nodal(cfg, _field)
+    om = OS.vorticity(cfg, u, tau)
+    ref = _nodal(cfg, _curl_field)
+    tol = 1e-8 if enriched else 1e-12
+    assert rel(om, ref) < tol
+
+
+def test_vorticity_enrichment_divergence_theorem():
+    """For u = psi u~ alone (tau_w uniform, so psi depends on y only) the
+    sum of a cell's polynomial rows is int_e grad psi x u~ = (psi(top) -
+    psi(bottom)) hx hz (e_y x u~), up to the quadrature error of psi'."""
+    wl = PRESETS["tiny"]
+    cfg = wl.mesh
+    tau = np.ones(cfg.n_tau)
+    n3 = (cfg.k_u + 1) ** 3
+    off = cfg.ncell * 3 * n3
+    ut = np.array([1.0, -0.4, 0.5])
+    u = np.zeros(cfg.n_vel)
+    for k in range(cfg.n_enriched):
+        u[off + 3 * k:off + 3 * k + 3] = ut
+    b = OS.vorticity_rhs(cfg, u, tau)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    for k, e in enumerate(O.enriched_cells(cfg)[:4]):
+        top = O.psi_point(cfg, tau, int(e), [0.5, 1.0, 0.5])[0]
+        bot = O.psi_point(cfg, tau, int(e), [0.5, 0.0, 0.5])[0]
+        dpsi = (top - bot) * hx * hz
+        sums = b[int(e) * 3 * n3:(int(e) + 1) * 3 * n3].reshape(3, n3).sum(axis=1)
+        expect = np.array([dpsi * ut[2], 0.0, -dpsi * ut[0]])
+        assert np.abs(sums - expect).max() < 2e-2 * np.abs(expect).max(), (sums, expect)
+
+
+def test_pressure_neumann_closed_form():
+    """Wall term of eq. bc_d_pres for u_x = d y + s x, u_y = a + b x + e x^2,
+    u_z = 0 (curl u = (0, 0, b + 2 e x - d), curl curl u . e_y = -2 e), two
+    time levels and a body force: per wall, the pressure rows sum to
+    int_wall h_N dA and, weighted with the nodal values of x, to
+    int_wall x h_N dA (Gauss-Legendre in x and z, exact for these degrees)."""
+    cfg = MeshConfig(nx=3, ny=3, nz=2, gamma=1.1, k_u=2, nq_u=4, k_p=1, nq_p=2, enrich_lower=0, enrich_upper=0,
+                     nu=1.0 / 50)
+    a, bb, ee, d, s = 0.3, -0.7, 0.25, 1.1, 0.4
+
+    def fld(X, Y, Z):
+        return np.array([d * Y + s * X, a + bb * X + ee * X * X, 0.0])
+
+    u1 = _nodal(cfg, fld)
+    u2 = 0.5 * u1
+    betas, f = (2.0, -1.0), (0.2, 0.9, -0.1)
+    om1, om2 = OS.vorticity(cfg, u1, None), OS.vorticity(cfg, u2, None)
+    rhs = OS.pressure_neumann(cfg, [u1, u2], [om1, om2], betas, f, None)
+
+    def conv_y(X, Y, sc):
+        ux, uy = sc * (d * Y + s * X), sc * (a + bb * X + ee * X * X)
+        return (sc * (bb + 2 * ee * X)) * ux + uy * (sc * s)
+
+    gx, wx = np.polynomial.legendre.leggauss(12)
+    xs, wxs = 0.5 * cfg.Lx * (gx + 1), 0.5 * cfg.Lx * wx
+    npp = cfg.k_p + 1
+    p3 = npp ** 3
+    glp = O.gauss_lobatto(npp)
+    hx = cfg.Lx / cfg.nx
+    for ey, Y, sg in ((0, -1.0, -1.0), (cfg.ny - 1, 1.0, 1.0)):
+        hN = np.zeros_like(xs)
+        for beta, sc in zip(betas, (1.0, 0.5)):
+            hN += beta * sg * (conv_y(xs, Y, sc) + cfg.nu * (-2 * ee * sc))
+        hN = -hN + sg * f[1]
+        want0 = (wxs * hN).sum() * cfg.Lz
+        want1 = (wxs * xs * hN).sum() * cfg.Lz
+        got0 = got1 = 0.0
+        for ez in range(cfg.nz):
+            for ex in range(cfg.nx):
+                e = ex + cfg.nx * (ey + cfg.ny * ez)
+                blk = rhs[e * p3:(e + 1) * p3]
+                got0 += blk.sum()
+                xn = np.array([(ex + glp[i]) * hx for m in range(npp) for j in range(npp) for i in range(npp)])
+                got1 += (blk * xn).sum()
+        assert abs(got0 - want0) < 1e-12 * max(1.0, abs(want0)), (got0, want0)
+        assert abs(got1 - want1) < 1e-12 * max(1.0, abs(want1)), (got1, want1)
+    # interior cells get nothing
+    e_mid = 0 + cfg.nx * (1 + cfg.ny * 0)
+    assert np.abs(rhs[e_mid * p3:(e_mid + 1) * p3]).max() == 0.0
