@@ -375,6 +375,39 @@ int dg_eddy_viscosity(const dg_mesh* mesh, const double* u, double c_des, double
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
 int dg_apply_viscous_multiscale(const dg_mesh* mesh, const double* nut, const double* u, double* out, void* stream);
 
+/* Right-hand side of the vorticity projection (paper Sec. 4.2: the
+ * vorticity omega_h of the pressure Neumann data is precomputed by L2
+ * projection onto the velocity space):
+ *   b(v) = (v, curl u)_e
+ * for every velocity test function (N_B e_c, and psi e_c in enriched cells),
+ * u = u_bar + psi u~ (so curl u includes grad psi x u~), the cell's velocity
+ * rule (nq_u^3; nq_u x nq_wn x nq_u in enriched cells).
+ *   u, b: device, dg_num_dofs(mesh, 0) doubles, distinct.  Flat walls only.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
+int dg_vorticity_rhs(const dg_mesh* mesh, const double* u, double* b, void* stream);
+
+/* omega = M^{-1} b with b from dg_vorticity_rhs: the L2 projection of curl u
+ * onto the enriched velocity space (the inverse mass matrix of
+ * dg_apply_inverse_mass).  u, omega: distinct device vectors. */
+int dg_vorticity(const dg_mesh* mesh, const double* u, double* omega, void* stream);
+
+/* Wall term of the pressure equation with the high-order Neumann data (paper
+ * Sec. 4.1 eq. bc_d_pres, the wall flux of eq. ipflux), ADDED into rhs:
+ *   rhs(q) += int_wall q h_N dA,
+ *   h_N = -( sum_i beta[i] (div(u_i (x) u_i) + nu curl omega_i) - f ) . n
+ * for the nhist (1 or 2) previous velocities u_i and their vorticities
+ * omega_i (dg_vorticity), n the outward wall normal (-e_y lower, +e_y upper
+ * wall), evaluated at the Gauss points of the velocity face rule (nq_u x
+ * nq_u) with u = u_bar + psi u~ (psi vanishes on the wall, grad psi does not)
+ * and tested with the pressure basis; only the wall cells' pressure rows
+ * change.  Nothing is added on a fully periodic box.
+ *   u, omega: host arrays of nhist device vectors (velocity layout);
+ *   beta: host, nhist extrapolation weights; f: host, body force (3
+ *   doubles, or NULL for none); rhs: device, dg_num_dofs(mesh, 1) doubles.
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved wall), DG_ERR_HIP. */
+int dg_pressure_neumann(const dg_mesh* mesh, int32_t nhist, const double* const* u, const double* const* omega,
+                        const double* beta, const double* f, double* rhs, void* stream);
+
 /* Restarted GMRES parameters and statistics of the Helmholtz step. */
 typedef struct {
   double rtol;          /* stop when ||gamma b - H x||_2 <= rtol ||gamma b||_2 (true residual, see below) */

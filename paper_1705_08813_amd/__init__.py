@@ -293,6 +293,43 @@ class Mesh:
         _lib.check(_lib.lib().dg_enrichment_active(self.handle, _dptr(out), _stream_ptr(stream)))
         return out[:self.n_enriched]
 
+    def vorticity_rhs(self, u, b=None, stream=None):
+        """dg_vorticity_rhs: b(v) = (v, curl u)_e."""
+        import torch
+        self._check_f64(u, self.n_vel, "u")
+        b = torch.empty_like(u) if b is None else b
+        self._check_f64(b, self.n_vel, "b")
+        _lib.check(_lib.lib().dg_vorticity_rhs(self.handle, _dptr(u), _dptr(b), _stream_ptr(stream)))
+        return b
+
+    def vorticity(self, u, omega=None, stream=None):
+        """dg_vorticity: the L2 projection of curl u onto the velocity space."""
+        import torch
+        self._check_f64(u, self.n_vel, "u")
+        omega = torch.empty_like(u) if omega is None else omega
+        self._check_f64(omega, self.n_vel, "omega")
+        _lib.check(_lib.lib().dg_vorticity(self.handle, _dptr(u), _dptr(omega), _stream_ptr(stream)))
+        return omega
+
+    def pressure_neumann(self, us, omegas, betas, f=(0.0, 0.0, 0.0), rhs=None, stream=None):
+        """dg_pressure_neumann: adds the wall term of the high-order pressure
+        Neumann data into rhs (zeros when None) and returns it."""
+        import torch
+        nh = len(us)
+        if nh != len(omegas) or nh != len(betas) or nh not in (1, 2):
+            raise ValueError("one or two (u, omega, beta) time levels")
+        for t in list(us) + list(omegas):
+            self._check_f64(t, self.n_vel, "u/omega")
+        rhs = torch.zeros(self.n_p, dtype=torch.float64, device=self.device) if rhs is None else rhs
+        self._check_f64(rhs, self.n_p, "rhs")
+        VP = ctypes.c_void_p
+        up = (VP * nh)(*[u.data_ptr() for u in us])
+        op = (VP * nh)(*[o.data_ptr() for o in omegas])
+        bp = (ctypes.c_double * nh)(*[float(b) for b in betas])
+        fp = (ctypes.c_double * 3)(*[float(v) for v in f])
+        _lib.check(_lib.lib().dg_pressure_neumann(self.handle, nh, up, op, bp, fp, _dptr(rhs), _stream_ptr(stream)))
+        return rhs
+
     def solve_helmholtz(self, nut, gamma0_over_dt, b, x=None, rtol=1e-12, max_iter=500, restart=30, workspace=None,
                         stream=None):
         """dg_solve_helmholtz: (gamma0/dt) M x + A(nut) x = (gamma0/dt) M b by

@@ -90,6 +90,11 @@ _SIGS = {
     "dg_apply_poisson": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "dg_poisson_diagonal": (ctypes.c_int, [_VP, _VP, _VP]),
     "dg_apply_convective": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "dg_vorticity_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "dg_vorticity": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "dg_pressure_neumann": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _VP,
+                                           _VP]),
     "dg_helmholtz_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.POINTER(GmresParams)]),
     "dg_solve_helmholtz": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, ctypes.POINTER(GmresParams), _VP,
                                           ctypes.c_size_t, ctypes.POINTER(GmresStats), _VP]),

@@ -246,6 +246,11 @@ int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* 
                            double* x, hipStream_t s);
 // x = M^{-1} r with the velocity mass matrix (flat meshes; x may be r)
 int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s);
+// vorticity right-hand side b(v) = (v, curl u)_e and the wall term of the
+// pressure Neumann data, added into rhs (kern_step.hip)
+int launch_vorticity_rhs(const dg_mesh* m, const double* u, double* b, hipStream_t s);
+int launch_pressure_neumann(const dg_mesh* m, int nh, const double* const* us, const double* const* oms,
+                            const double* beta, const double* f, double* rhs, hipStream_t s);
 // Helmholtz step (helmholtz.hip): workspace bytes and the restarted GMRES solve
 int64_t helmholtz_workspace_bytes(const dg_mesh* m, int restart);
 int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const double* b, double* x, double rtol,

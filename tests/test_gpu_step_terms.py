@@ -1,0 +1,115 @@
+"""GPU vorticity projection and pressure Neumann data (Sec. 4.1 eq.
+bc_d_pres, Sec. 4.2) against the CPU oracle, through the C ABI.
+
+Vorticity right-hand side and the wall term: FP64 at 1e-12 of the largest
+oracle value (polynomial and enrichment rows separately).  The projected
+vorticity omega = M^{-1} b is checked by its backward error with the
+oracle's forward mass matrix, ||M omega - b|| <= 1e-12 (||M|| ||omega|| +
+||b||) per row block, since the enriched cells' mass blocks are
+ill-conditioned.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import project as OP
+from oracle import step as OS
+from paper_1705_08813_amd import DgError, Mesh
+from paper_1705_08813_amd.inputs import PRESETS, MeshConfig, Workload, draw_inputs
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "tiny": PRESETS["tiny"],
+    "k2_stretched": Workload("v2", MeshConfig(nx=3, ny=4, nz=2, gamma=1.3, k_u=2, nq_u=4, k_p=1, nq_p=2), 51, 0.5, 1.5),
+    "k4_lower": Workload("v4", MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=4, nq_u=7, enrich_upper=0), 52, 0.5, 1.5),
+    "k5": Workload("v5", MeshConfig(nx=2, ny=3, nz=2, gamma=0.8, k_u=5, nq_u=8, k_p=4, nq_p=5), 53, 0.2, 2.0),
+    "k3_vandriest": Workload("v3d", MeshConfig(nx=3, ny=3, nz=2, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3, psi_kind=1),
+                             54, 0.5, 1.5),
+    "k3_switch_off": Workload("v3s", MeshConfig(nx=3, ny=3, nz=2, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3,
+                                                yplus_off=60.0), 55, 0.5, 1.5),
+    "k3_plain": Workload("v3p", MeshConfig(nx=3, ny=3, nz=2, gamma=1.1, k_u=3, nq_u=5, k_p=2, nq_p=3, enrich_lower=0,
+                                           enrich_upper=0), 56, 1.0, 1.0),
+    "k3_periodic": Workload("v3q", MeshConfig(nx=3, ny=3, nz=2, k_u=3, nq_u=5, nq_wn=8, fully_periodic=1), 57, 1, 1),
+}
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _split(cfg, v):
+    n = cfg.ncell * 3 * (cfg.k_u + 1) ** 3
+    return v[:n], v[n:]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vorticity_matches_oracle(name):
+    wl = CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] vorticity case={name}")
+    inp = draw_inputs(wl)
+    tau = inp["tau"] if cfg.n_enriched else None
+    mesh = Mesh(cfg, inp["tau"])
+    ut = torch.tensor(inp["u"], device="cuda")
+    b = mesh.vorticity_rhs(ut).cpu().numpy()
+    ref = OS.vorticity_rhs(cfg, inp["u"], tau)
+    bp, be = _split(cfg, b)
+    rp, re = _split(cfg, ref)
+    _log(f"[gpu]   rhs rel poly {_rel(bp, rp):.1e}" + (f" enr {_rel(be, re):.1e}" if re.size else ""))
+    assert _rel(bp, rp) <= 1e-12
+    if re.size:
+        assert _rel(be, re) <= 1e-12
+    om = mesh.vorticity(ut).cpu().numpy()
+    psi = O.psi_volume(cfg, O.enriched_cells(cfg), tau=tau) if cfg.n_enriched else np.zeros((0, 1))
+    back = OP.mass_apply(cfg, om, psi) - ref
+    scale = np.abs(ref).max() + np.abs(OP.mass_apply(cfg, np.abs(om), np.abs(psi))).max()
+    _log(f"[gpu]   omega backward error {np.abs(back).max() / scale:.1e}")
+    assert np.abs(back).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name", [n for n in CASES if n != "k3_periodic"])
+def test_pressure_neumann_matches_oracle(name):
+    wl = CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] pressure Neumann case={name}")
+    inp = draw_inputs(wl)
+    tau = inp["tau"] if cfg.n_enriched else None
+    rng = np.random.default_rng(58)
+    u1 = inp["u"]
+    u2 = rng.uniform(-1, 1, cfg.n_vel)
+    mesh = Mesh(cfg, inp["tau"])
+    us = [torch.tensor(u1, device="cuda"), torch.tensor(u2, device="cuda")]
+    oms = [mesh.vorticity(u) for u in us]
+    base = rng.uniform(-1, 1, cfg.n_p)
+    f = (0.3, -0.7, 0.2)
+    rhs = mesh.pressure_neumann(us, oms, (2.0, -1.0), f, rhs=torch.tensor(base, device="cuda")).cpu().numpy()
+    om_np = [o.cpu().numpy() for o in oms]                 # the GPU vorticities feed both sides
+    ref = OS.pressure_neumann(cfg, [u1, u2], om_np, (2.0, -1.0), f, tau)
+    err = _rel(rhs - base, ref)
+    _log(f"[gpu]   rel err {err:.1e}, |ref| {np.abs(ref).max():.2e}")
+    assert err <= 1e-12
+    # one time level, no force
+    r1 = mesh.pressure_neumann(us[:1], oms[:1], (1.0,), (0.0, 0.0, 0.0)).cpu().numpy()
+    ref1 = OS.pressure_neumann(cfg, [u1], om_np[:1], (1.0,), (0.0, 0.0, 0.0), tau)
+    assert _rel(r1, ref1) <= 1e-12
+
+
+def test_periodic_box_and_errors():
+    wl = CASES["k3_periodic"]
+    mesh = Mesh(wl.mesh, draw_inputs(wl)["tau"])
+    u = torch.tensor(draw_inputs(wl)["u"], device="cuda")
+    om = mesh.vorticity(u)
+    assert float(mesh.pressure_neumann([u], [om], (1.0,)).abs().max()) == 0.0   # no walls: nothing added
+    with pytest.raises(ValueError):
+        mesh.pressure_neumann([u, u, u], [om, om, om], (1.0, 1.0, 1.0))
+    curved = Mesh(MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3))
+    uc = torch.zeros(curved.n_vel, dtype=torch.float64, device="cuda")
+    with pytest.raises(DgError) as ei:
+        curved.vorticity(uc)
+    assert ei.value.code == -6
