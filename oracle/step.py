@@ -170,3 +170,50 @@ def pressure_neumann(cfg, us, omegas, betas, f, tau):
                     Np = np.einsum("m,j,i->mji", vz, vy, vx).reshape(-1)
                     rhs[e * p3:(e + 1) * p3] += wts[qi] * hn[qi] * Np
     return rhs
+
+
+def dual_splitting_step(cfg, tau, u_n, u_nm1, dt, order=2, f=(0.0, 0.0, 0.0), dt_over_cr=None,
+                        c_des=0.85, beta_des=6.0, helm_rtol=1e-11):
+    """One step of the dual-splitting scheme (Sec. 4.1; the element-wise forms
+    of Sec. 4.2), each step from the oracle's operators, in the paper's order:
+    convective step (eq. convstepspat), pressure Poisson equation with the
+    high-order Neumann data (eqs. poissonspat, ipflux, bc_d_pres; dense
+    least squares, zero mean), projection (eq. projectionspat, tau_D from
+    u^n), Helmholtz step (eq. helmholtzspat, nu_t from u^n).  Constant-step
+    BDF/extrapolation coefficients of order 1 or 2.  Returns (u^{n+1}, p,
+    u_hat, u_hathat)."""
+    from . import convective_residual, divdiv_tau, pressure_gradient, velocity_divergence
+    from . import solve as osolve
+    from .project import projection_step
+    if order == 2:
+        g0, al, be = 1.5, (2.0, -0.5), (2.0, -1.0)
+        us = [np.asarray(u_n, dtype=np.float64), np.asarray(u_nm1, dtype=np.float64)]
+    else:
+        g0, al, be = 1.0, (1.0,), (1.0,)
+        us = [np.asarray(u_n, dtype=np.float64)]
+    dt_over_cr = dt / 0.14 if dt_over_cr is None else dt_over_cr
+    n3 = (cfg.k_u + 1) ** 3
+    off = cfg.ncell * 3 * n3
+    psi = _psi(cfg, tau)
+    # 1 convective step; M^{-1} (v, f) of a constant f is f on the polynomial unknowns
+    s = sum(b * convective_residual(cfg, u, tau) for b, u in zip(be, us))
+    u_hat = (sum(a * u for a, u in zip(al, us)) - dt * inverse_mass(cfg, s, psi)) / g0
+    fpoly = np.zeros(cfg.n_vel)
+    for c in range(3):
+        for e in range(cfg.ncell):
+            fpoly[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = f[c]
+    u_hat += dt / g0 * fpoly
+    # 2 pressure
+    oms = [vorticity(cfg, u, tau) for u in us]
+    rhs = -(g0 / dt) * velocity_divergence(cfg, u_hat, tau=tau) + pressure_neumann(cfg, us, oms, be, f, tau)
+    p = osolve.dense_solution(cfg, rhs)
+    # 3 projection
+    g = pressure_gradient(cfg, p, tau=tau)
+    tau_d = divdiv_tau(cfg, us[0], dt_over_cr, tau=tau)
+    cells = enriched_cells(cfg)
+    psi4 = psi_volume4(cfg, cells, tau=tau) if cells.size else np.zeros((0, 1, 4))
+    u_hh = projection_step(cfg, u_hat, g, dt / g0, tau_d, psi4)
+    # 4 Helmholtz
+    u_np1, _ = helmholtz_solve(cfg, us[0], tau, g0 / dt, u_hh, rtol=helm_rtol)
+    del off
+    return u_np1, p, u_hat, u_hh

@@ -182,3 +182,47 @@ def test_pressure_neumann_closed_form():
     # interior cells get nothing
     e_mid = 0 + cfg.nx * (1 + cfg.ny * 0)
     assert np.abs(rhs[e_mid * p3:(e_mid + 1) * p3]).max() == 0.0
+
+
+def test_step_zero_state_stays_zero():
+    wl = PRESETS["tiny"]
+    cfg = wl.mesh
+    tau = draw_inputs(wl)["tau"]
+    z = np.zeros(cfg.n_vel)
+    u1, p, _, _ = OS.dual_splitting_step(cfg, tau, z, z, 0.01)
+    assert np.abs(u1).max() == 0.0 and np.abs(p).max() < 1e-14
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_step_body_force_from_rest_periodic(order):
+    """No walls, no enrichment, u = 0: the step gives the constant dt/gamma0 f
+    (C annihilates it, D vanishes with tau_D(0) = 0, A annihilates constants)
+    and a zero pressure."""
+    cfg = MeshConfig(nx=3, ny=2, nz=2, gamma=0.0, k_u=2, nq_u=4, k_p=1, nq_p=2, fully_periodic=1)
+    z = np.zeros(cfg.n_vel)
+    f = (0.8, -0.3, 0.5)
+    dt = 0.02
+    u1, p, _, _ = OS.dual_splitting_step(cfg, None, z, z, dt, order=order, f=f)
+    g0 = 1.5 if order == 2 else 1.0
+    n3 = (cfg.k_u + 1) ** 3
+    want = np.zeros(cfg.n_vel)
+    for c in range(3):
+        for e in range(cfg.ncell):
+            want[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = dt / g0 * f[c]
+    assert rel(u1, want) < 1e-11
+    assert np.abs(p).max() < 1e-12
+
+
+def test_step_projection_reduces_divergence():
+    """The pressure and projection steps remove most of the divergence of the
+    intermediate velocity (the purpose of eqs. poissonspat/projectionspat)."""
+    wl = PRESETS["tiny"]
+    cfg = wl.mesh
+    inp = draw_inputs(wl)
+    rng = np.random.default_rng(9)
+    u0 = 0.3 * inp["u"]
+    u1 = 0.3 * rng.uniform(-1, 1, cfg.n_vel)
+    _, _, uh, uhh = OS.dual_splitting_step(cfg, inp["tau"], u0, u1, 0.005)
+    d0 = np.linalg.norm(O.velocity_divergence(cfg, uh, tau=inp["tau"]))
+    d1 = np.linalg.norm(O.velocity_divergence(cfg, uhh, tau=inp["tau"]))
+    assert d1 < 0.2 * d0, (d0, d1)
