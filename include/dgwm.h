@@ -606,6 +606,52 @@ int dg_solve_poisson_batched(const dg_mesh* const* meshes, int32_t n, const dg_s
                              dg_solve_stats* stats, int32_t* codes, void* batch_ws, size_t batch_ws_bytes,
                              void* stream);
 
+/* ------------------------------------------------- dual-splitting step --- */
+
+typedef struct {
+  double dt;             /* time step                                                            */
+  double gamma0;         /* BDF coefficient of the new level (BDF2: 3/2; BDF1: 1)                */
+  double alpha[2];       /* coefficients of u^n, u^{n-1} (BDF2: 2, -1/2; BDF1: 1, 0)             */
+  double beta[2];        /* extrapolation of F^c and of the Neumann data (EXT2: 2, -1; 1, 0)    */
+  int32_t order;         /* time levels J = 1 or 2                                               */
+  double f[3];           /* constant body force (e.g. the channel's driving pressure gradient)   */
+  double dt_over_cr;     /* div-div penalty parameter dt/Cr of eq. tauD                          */
+  double c_des, beta_des;/* eddy viscosity constants of eq. ydes (paper: 0.85, 6)                */
+  dg_solve_params poisson;
+  dg_gmres_params helmholtz;
+} dg_step_params;
+
+typedef struct {
+  dg_solve_stats poisson;
+  dg_gmres_stats helmholtz;
+  double seconds;        /* host wall time of the step                                           */
+} dg_step_stats;
+
+/* Device workspace of dg_dual_splitting_step (7 velocity vectors, the
+ * pressure right-hand side, tau_D, nu_t, the Poisson and Helmholtz solver
+ * workspaces), or a negative DG_ERR_* code. */
+int64_t dg_step_workspace_bytes(const dg_mesh* mesh, const dg_step_params* sp);
+
+/* One time step of the dual-splitting scheme (paper Sec. 4.1; element-wise
+ * forms of Sec. 4.2), every operator on the GPU:
+ *   1 convective step (eq. convstepspat):
+ *       u^ = (sum_i alpha_i u^{n-i} - dt M^{-1} sum_i beta_i F^c(u^{n-i})) / gamma0 + dt/gamma0 f
+ *   2 pressure (eq. poissonspat with eq. ipflux on the walls): A p = -(gamma0/dt) C u^
+ *       + int_wall q h_N, h_N the high-order Neumann data of eq. bc_d_pres from u^{n-i} and
+ *       their projected vorticities; solved by dg_solve_poisson with sp->poisson (p holds the
+ *       initial guess on entry, e.g. the previous pressure, and the zero-mean p^{n+1} on exit)
+ *   3 projection (eq. projectionspat): (M + D) u^^ = M u^ - dt/gamma0 P p, tau_D from u^n
+ *   4 Helmholtz (eq. helmholtzspat): (gamma0/dt) M u + A(nu_t) u = (gamma0/dt) M u^^ by
+ *       dg_solve_helmholtz with sp->helmholtz, nu_t from the enrichment of u^n, from u^^
+ * The wall shear stress and psi are those of the mesh (a caller refreshes them between
+ * steps with dg_wall_shear_nodes / dg_update_wall_shear_nodes / dg_project_velocity).
+ *   u_n, u_nm1 (order 2 only), u_np1: device velocity vectors, u_np1 distinct from both;
+ *   p: device pressure vector; ws: >= dg_step_workspace_bytes.
+ *   Errors: those of the steps (DG_ERR_NOT_CONVERGED from either solver, stats filled),
+ *   DG_ERR_ARG, DG_ERR_WORKSPACE, DG_ERR_UNSUPPORTED (curved wall), DG_ERR_HIP. */
+int dg_dual_splitting_step(const dg_mesh* mesh, const dg_step_params* sp, const double* u_n, const double* u_nm1,
+                           double* u_np1, double* p, void* ws, size_t ws_bytes, dg_step_stats* stats, void* stream);
+
 /* ---------------------------------------------------------------- misc --- */
 
 const char* dg_last_error(void);

@@ -350,6 +350,44 @@ class Mesh:
                                                  _stream_ptr(stream)))
         return x, st
 
+    def step_params(self, dt, order=2, f=(0.0, 0.0, 0.0), dt_over_cr=None, poisson=None, helmholtz_rtol=1e-10,
+                    helmholtz_max_iter=1000, helmholtz_restart=30, c_des=0.85, beta_des=6.0):
+        """dg_step_params with the constant-step BDF/extrapolation coefficients
+        of order 1 or 2 (gamma0 = 3/2, alpha = (2, -1/2), beta = (2, -1) for
+        order 2); dt_over_cr defaults to dt / 0.14 (the paper's Courant number)."""
+        if order == 2:
+            g0, al, be = 1.5, (2.0, -0.5), (2.0, -1.0)
+        elif order == 1:
+            g0, al, be = 1.0, (1.0, 0.0), (1.0, 0.0)
+        else:
+            raise ValueError("order must be 1 or 2")
+        sp = poisson if poisson is not None else self.solve_params(rtol=1e-10, mixed=True)
+        return _lib.StepParams(dt=dt, gamma0=g0, alpha=(ctypes.c_double * 2)(*al), beta=(ctypes.c_double * 2)(*be),
+                               order=order, f=(ctypes.c_double * 3)(*f),
+                               dt_over_cr=dt / 0.14 if dt_over_cr is None else dt_over_cr, c_des=c_des,
+                               beta_des=beta_des, poisson=sp,
+                               helmholtz=_lib.GmresParams(rtol=helmholtz_rtol, max_iter=helmholtz_max_iter,
+                                                          restart=helmholtz_restart))
+
+    def dual_splitting_step(self, sp, u_n, u_nm1, p, u_np1=None, workspace=None, stream=None):
+        """dg_dual_splitting_step: returns (u_np1, p, StepStats); p is updated in place."""
+        import torch
+        self._check_f64(u_n, self.n_vel, "u_n")
+        if sp.order == 2:
+            self._check_f64(u_nm1, self.n_vel, "u_nm1")
+        self._check_f64(p, self.n_p, "p")
+        u_np1 = torch.empty_like(u_n) if u_np1 is None else u_np1
+        self._check_f64(u_np1, self.n_vel, "u_np1")
+        if workspace is None:
+            nb = _lib.check(_lib.lib().dg_step_workspace_bytes(self.handle, ctypes.byref(sp)))
+            workspace = torch.empty(int(nb), dtype=torch.uint8, device=self.device)
+        st = _lib.StepStats()
+        _lib.check(_lib.lib().dg_dual_splitting_step(self.handle, ctypes.byref(sp), _dptr(u_n),
+                                                     _dptr(u_nm1) if u_nm1 is not None else None, _dptr(u_np1),
+                                                     _dptr(p), _dptr(workspace), workspace.numel(), ctypes.byref(st),
+                                                     _stream_ptr(stream)))
+        return u_np1, p, st
+
     def solve_params(self, rtol=1e-10, mixed=True, max_outer=2000, max_inner=0, cheb_degree=5,
                      multigrid=True, coarse_degree=3):
         return SolveParams(rtol=rtol, max_outer=max_outer, max_inner=max_inner, cheb_degree=cheb_degree,

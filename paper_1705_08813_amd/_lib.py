@@ -59,6 +59,17 @@ class SolveStats(ctypes.Structure):
                 ("rel_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
+class StepParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("gamma0", ctypes.c_double), ("alpha", ctypes.c_double * 2),
+                ("beta", ctypes.c_double * 2), ("order", ctypes.c_int32), ("f", ctypes.c_double * 3),
+                ("dt_over_cr", ctypes.c_double), ("c_des", ctypes.c_double), ("beta_des", ctypes.c_double),
+                ("poisson", SolveParams), ("helmholtz", GmresParams)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("poisson", SolveStats), ("helmholtz", GmresStats), ("seconds", ctypes.c_double)]
+
+
 # every symbol include/dgwm.h declares, with its signature
 _VP = ctypes.c_void_p
 _SIGS = {
@@ -96,6 +107,9 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _VP,
                                            _VP]),
     "dg_helmholtz_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.POINTER(GmresParams)]),
+    "dg_step_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.POINTER(StepParams)]),
+    "dg_dual_splitting_step": (ctypes.c_int, [_VP, ctypes.POINTER(StepParams), _VP, _VP, _VP, _VP, _VP,
+                                              ctypes.c_size_t, ctypes.POINTER(StepStats), _VP]),
     "dg_solve_helmholtz": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, ctypes.POINTER(GmresParams), _VP,
                                           ctypes.c_size_t, ctypes.POINTER(GmresStats), _VP]),
     "dg_mg_levels": (ctypes.c_int, [_VP, _VP, ctypes.c_int32]),
