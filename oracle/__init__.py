@@ -36,6 +36,7 @@ class OrcParams(ctypes.Structure):
         ("ip_factor_u", ctypes.c_double), ("ip_factor_p", ctypes.c_double),
         ("wall_ip_mult", ctypes.c_double), ("theta", ctypes.c_double),
         ("psi_kind", ctypes.c_int32), ("A_plus", ctypes.c_double), ("yplus_off", ctypes.c_double),
+        ("enrich_degree", ctypes.c_int32),
     ]
 
 
@@ -99,8 +100,17 @@ def params(cfg) -> OrcParams:
     d = cfg if isinstance(cfg, dict) else cfg.as_dict()
     p = OrcParams()
     for name, _ in OrcParams._fields_:
-        setattr(p, name, d[name])
+        setattr(p, name, d.get(name, 0) if name == "enrich_degree" else d[name])
     return p
+
+
+def require_l0(cfg):
+    """The operators other than the velocity residual (and its convective
+    form) are built for constant enrichment weights, l = 0 of Sec. 3.1 eq.
+    enrichment."""
+    d = cfg if isinstance(cfg, dict) else cfg.as_dict()
+    if d.get("enrich_degree", 0) != 0:
+        raise NotImplementedError("this oracle operator is built for l = 0 enrichment weights only")
 
 
 def _ptr(a):
@@ -176,7 +186,9 @@ def _cells(cfg, cells):
 
 def velocity_residual(cfg, u, tau, cells=None, absmode=False):
     """Residual r for the listed cells (others left zero).  Layout
-    [cell][component][node] then [enriched cell][component]."""
+    [cell][component][node] then [enriched cell][component][enrichment node]
+    ((l+1)^3 enrichment nodes: 1 for l = 0, 8 trilinear vertex functions
+    for l = 1, node bx + 2 (by + 2 bz))."""
     p = params(cfg)
     u = _f64(u)
     n = num_dofs(cfg, 0)

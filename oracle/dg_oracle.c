@@ -58,6 +58,7 @@ typedef struct {
   double A_plus;    /* van Driest damping constant A+ */
   double yplus_off; /* > 0: the enrichment of a wall cell is off while every quadrature point of
                        the cell has y+ below this value (Sec. 3.2: 30); 0: always on */
+  int32_t enrich_degree; /* tensor degree l of the enrichment weights (Sec. 3.1, eq. enrichment): 0 or 1 */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -231,6 +232,7 @@ typedef struct {
   const double *tau_nodes; /* or: nodal wall shear stress [wall][nz][nx] (Sec. 3.2, m = 1) */
   signed char *act;   /* per enriched cell: 1 enrichment on, 0 off; NULL: all on */
   int conv_only;      /* velocity residual: 1 keeps the convective terms alone */
+  int nle;            /* enrichment shape functions per component: (l+1)^3 = 1 or 8 */
 } ctx;
 
 /* Wall-normal vertex coordinate, Sec. 5.1: f(t) = tanh(gamma(2t-1))/tanh(gamma). */
@@ -525,6 +527,9 @@ typedef struct {
   double u[3], g[3][3];   /* velocity and g[c][d] = d u_c / d x_d */
   psi_pt psi;             /* valid if enriched */
   int enriched;
+  /* valid if enriched: the enrichment functions psi N^l_B (B < (l+1)^3) and
+   * their physical gradients N^l_B grad psi + psi grad N^l_B */
+  double ev[8], eg[8][3];
 } vel_pt;
 
 /* Tensor-product basis of degree n-1 at xi, physical gradients via J^{-T}. */
@@ -544,7 +549,27 @@ static void basis3(int n, const double *nodes, const double xi[3], const double 
       }
 }
 
-/* u_h = sum_B N_B u_B + psi * u~ (l = 0) and its gradient at xi of cell e.
+/* Enrichment functions of an enriched cell at xi (Sec. 3.1, eq.
+ * enrichment): psi N^l_B with N^l_B the tensor-product Lagrange functions of
+ * degree l on the nodes {0, 1} (l = 1: the trilinear vertex functions,
+ * B = bx + 2 (by + 2 bz); l = 0: the constant 1), and their gradients. */
+static void enr_basis(const ctx *C, const double xi[3], const double Ji[3][3], const psi_pt *ps, double *ev,
+                      double (*eg)[3]) {
+  if (C->nle == 1) {
+    ev[0] = ps->psi;
+    for (int d = 0; d < 3; ++d) eg[0][d] = ps->g[d];
+    return;
+  }
+  static const double v01[2] = {0.0, 1.0};
+  double nb[8], ng[8][3];
+  basis3(2, v01, xi, Ji, nb, ng);
+  for (int B = 0; B < 8; ++B) {
+    ev[B] = ps->psi * nb[B];
+    for (int d = 0; d < 3; ++d) eg[B][d] = nb[B] * ps->g[d] + ps->psi * ng[B][d];
+  }
+}
+
+/* u_h = sum_B N_B u_B + psi sum_B N^l_B u~_B and its gradient at xi of cell e.
  * absmode: every product and sum taken in absolute value (rounding bounds). */
 static void eval_vel(const ctx *C, const double *u, int64_t e, const double xi[3], const double Ji[3][3],
                      int absmode, vel_pt *out, double *bv, double (*bg)[3]) {
@@ -567,13 +592,16 @@ static void eval_vel(const ctx *C, const double *u, int64_t e, const double xi[3
   out->enriched = (C->enr[e] >= 0);
   if (out->enriched) {
     eval_psi(C, e, xi, Ji, &out->psi);
-    const double *ut = u + C->ncell * 3 * np3 + C->enr[e] * 3;
-    for (int c = 0; c < 3; ++c) {
-      double uc = absmode ? fabs(ut[c]) : ut[c];
-      double ps = absmode ? fabs(out->psi.psi) : out->psi.psi;
-      out->u[c] += ps * uc;
-      for (int d = 0; d < 3; ++d) out->g[c][d] += uc * (absmode ? fabs(out->psi.g[d]) : out->psi.g[d]);
-    }
+    enr_basis(C, xi, Ji, &out->psi, out->ev, out->eg);
+    const int nle = C->nle;
+    const double *ut = u + C->ncell * 3 * np3 + C->enr[e] * 3 * nle;  /* [c][B] */
+    for (int c = 0; c < 3; ++c)
+      for (int B = 0; B < nle; ++B) {
+        double uc = absmode ? fabs(ut[c * nle + B]) : ut[c * nle + B];
+        double ps = absmode ? fabs(out->ev[B]) : out->ev[B];
+        out->u[c] += ps * uc;
+        for (int d = 0; d < 3; ++d) out->g[c][d] += uc * (absmode ? fabs(out->eg[B][d]) : out->eg[B][d]);
+      }
   }
 }
 
@@ -589,6 +617,8 @@ static int ctx_init(ctx *C, const orc_params *P, const double *tau) {
   if (P->k_u < 1 || P->k_u + 1 > ORC_MAXN || P->k_p < 1 || P->k_p + 1 > ORC_MAXN) return -1;
   if (P->nq_u < 1 || P->nq_u > ORC_MAXN || P->nq_wn < 1 || P->nq_wn > ORC_MAXN ||
       P->nq_p < 1 || P->nq_p > ORC_MAXN) return -1;
+  if (P->enrich_degree != 0 && P->enrich_degree != 1) return -1;
+  C->nle = P->enrich_degree ? 8 : 1;
   C->ncell = (int64_t)P->nx * P->ny * P->nz;
   C->eta = (double *)malloc(sizeof(double) * (P->ny + 1));
   C->enr = (int64_t *)malloc(sizeof(int64_t) * C->ncell);
@@ -616,11 +646,18 @@ static void ctx_free(ctx *C) {
   free(C->act);
 }
 
+/* Operators built for constant enrichment weights (l = 0) only. */
+static int ctx_init_l0(ctx *C, const orc_params *P, const double *tau) {
+  if (ctx_init(C, P, tau)) return -1;
+  if (C->nle != 1) { ctx_free(C); return -1; }
+  return 0;
+}
+
 int64_t orc_num_dofs(const orc_params *P, int field) {
   ctx C;
   if (ctx_init(&C, P, NULL)) return -1;
   int64_t n;
-  if (field == 0) n = C.ncell * 3 * C.npu * C.npu * C.npu + C.nenr * 3;
+  if (field == 0) n = C.ncell * 3 * C.npu * C.npu * C.npu + C.nenr * 3 * C.nle;
   else n = C.ncell * C.npp * C.npp * C.npp;
   ctx_free(&C);
   return n;
@@ -639,7 +676,7 @@ int64_t orc_num_enriched(const orc_params *P) {
 /* ------------------------------------------------------------------------ */
 
 /* Residual of cell e for every test function of e (polynomial N_B e_c and,
- * if enriched, psi e_c):
+ * if enriched, psi N^l_B e_c):
  *   r(phi) = (grad phi, 2 nu eps(u) - u (x) u)_e
  *          + sum_F ( phi . f_v + grad phi : F_g )_F
  *   f_v = 1/2 (u- (u-.n) + u+ (u+.n)) + Lambda/2 (u- - u+)
@@ -655,7 +692,8 @@ static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int ab
    * keeps the physical nu through y+) */
   double nu = C->conv_only ? 0.0 : C->P.nu, theta = C->P.theta;
   double *re = r + (int64_t)e * 3 * np3;
-  double rt[3] = {0, 0, 0};
+  const int nle = C->nle;
+  double rt[3 * 8] = {0};  /* enrichment rows [c][B] */
   for (int i = 0; i < 3 * np3; ++i) re[i] = 0.0;
 
   /* volume */
@@ -684,7 +722,8 @@ static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int ab
               rc[B] += wq * s;
             }
             if (p.enriched)
-              for (int d = 0; d < 3; ++d) rt[c] += wq * (absmode ? fabs(p.psi.g[d]) : p.psi.g[d]) * G[c][d];
+              for (int B = 0; B < nle; ++B)
+                for (int d = 0; d < 3; ++d) rt[c * nle + B] += wq * (absmode ? fabs(p.eg[B][d]) : p.eg[B][d]) * G[c][d];
           }
         }
   }
@@ -776,17 +815,18 @@ static void vel_cell(const ctx *C, const double *u, int64_t e, double *r, int ab
             for (int k = 0; k < 3; ++k) sv += (absmode ? fabs(bg[B][k]) : bg[B][k]) * Fg[c][k];
             rc[B] += wf * sv;
           }
-          if (pm.enriched) {
-            double sv = (absmode ? fabs(pm.psi.psi) : pm.psi.psi) * fv[c];
-            for (int k = 0; k < 3; ++k) sv += (absmode ? fabs(pm.psi.g[k]) : pm.psi.g[k]) * Fg[c][k];
-            rt[c] += wf * sv;
-          }
+          if (pm.enriched)
+            for (int B = 0; B < nle; ++B) {
+              double sv = (absmode ? fabs(pm.ev[B]) : pm.ev[B]) * fv[c];
+              for (int k = 0; k < 3; ++k) sv += (absmode ? fabs(pm.eg[B][k]) : pm.eg[B][k]) * Fg[c][k];
+              rt[c * nle + B] += wf * sv;
+            }
         }
       }
   }
   if (C->enr[e] >= 0) {
-    double *ro = r + C->ncell * 3 * np3 + C->enr[e] * 3;
-    for (int c = 0; c < 3; ++c) ro[c] = rt[c];
+    double *ro = r + C->ncell * 3 * np3 + C->enr[e] * 3 * nle;
+    for (int i = 0; i < 3 * nle; ++i) ro[i] = rt[i];
   }
 }
 
@@ -995,7 +1035,7 @@ static void div_cell(const ctx *C, const double *u, int64_t e, double *out, doub
 static int mixed_op(const orc_params *P, const double *in, const double *tau_w, const double *tau_nodes,
                     const int64_t *cells, int64_t ncells, double *out, int divergence) {
   ctx C;
-  if (ctx_init(&C, P, tau_w)) return -1;
+  if (ctx_init_l0(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
@@ -1043,7 +1083,7 @@ int orc_velocity_divergence(const orc_params *P, const double *u, const double *
 int orc_divdiv_tau(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
                    double dt_over_cr, const int64_t *cells, int64_t ncells, double *tau_d) {
   ctx C;
-  if (ctx_init(&C, P, tau_w)) return -1;
+  if (ctx_init_l0(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
@@ -1088,7 +1128,7 @@ int orc_divdiv_tau(const orc_params *P, const double *u, const double *tau_w, co
 int orc_divdiv_apply(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
                      const double *tau_d, const int64_t *cells, int64_t ncells, double *out) {
   ctx C;
-  if (ctx_init(&C, P, tau_w)) return -1;
+  if (ctx_init_l0(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
@@ -1390,7 +1430,7 @@ int orc_wall_shear_nodes(const orc_params *P, const double *u, const double *tau
                          double *out) {
   ctx C;
   if (P->fully_periodic || P->wall_amp != 0.0) return -3;
-  if (ctx_init(&C, P, tau_w)) return -1;
+  if (ctx_init_l0(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
@@ -1561,7 +1601,8 @@ static void visc_ms_cell(const ctx *C, const double *u, const double *unut, int6
   int n = C->npu, np3 = n * n * n;
   double nu = C->P.nu;
   double *re = r + (int64_t)e * 3 * np3;
-  double rt[3] = {0, 0, 0};
+  const int nle = C->nle;
+  double rt[3 * 8] = {0};  /* enrichment rows [c][B] */
   for (int i = 0; i < 3 * np3; ++i) re[i] = 0.0;
   int e_enr = C->enr[e] >= 0;
 
@@ -1690,7 +1731,7 @@ int orc_viscous_multiscale(const orc_params *P, const double *u, const double *u
                            const double *tau_nodes, double c_des, double beta, int clip, const int64_t *cells,
                            int64_t ncells, double *r) {
   ctx C;
-  if (ctx_init(&C, P, tau_w)) return -1;
+  if (ctx_init_l0(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   if (P->wall_amp != 0.0) { ctx_free(&C); return -4; }
@@ -1720,7 +1761,7 @@ int orc_viscous_multiscale(const orc_params *P, const double *u, const double *u
 int orc_eddy_viscosity_point(const orc_params *P, const double *u_nut, const double *tau_w, const double *tau_nodes,
                              double c_des, double beta, int64_t e, const double *xi, double *out4) {
   ctx C;
-  if (ctx_init(&C, P, tau_w)) return -1;
+  if (ctx_init_l0(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (e < 0 || e >= C.ncell || C.enr[e] < 0 || P->wall_amp != 0.0) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);

@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import enriched_cells, gauss, gauss_lobatto, lagrange, vertex_eta
+from . import enriched_cells, gauss, gauss_lobatto, lagrange, require_l0, vertex_eta
 
 
 def volume_rule(cfg):
@@ -63,6 +63,7 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
     volume rule.  With return_cond, also the 2-norm condition number of each
     enriched cell's mass matrix.  only: enriched-cell positions to project
     (the projection is cell-local; the others keep u_old)."""
+    require_l0(cfg)
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -114,6 +115,7 @@ def l2_normal_equation(cfg, k, u_old, psi_old_k, psi_new_k):
     """Eq. l2 of enriched cell k written as its normal equation A x_c = b_c per
     component c: A = Phi^T W Phi (the new local mass matrix), b_c = Phi^T W u_old,c,
     and babs_c = |Phi|^T W |u_old,c| (a bound on the rounding of b_c)."""
+    require_l0(cfg)
     cells = enriched_cells(cfg)
     pts, wts = volume_rule(cfg)
     V = basis_at(cfg, pts)
@@ -137,6 +139,7 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     operator is block diagonal; the others are left at 0).  With return_cond,
     also the 2-norm condition number of each cell's block (0 for cells not
     inverted).  Flat (box) meshes only."""
+    require_l0(cfg)
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -170,6 +173,7 @@ def mass_apply(cfg, x, psi):
     """y = M x with the velocity mass matrix of every cell (the forward
     operator that inverse_mass inverts; same blocks, same psi convention:
     zero rows switch a cell's enrichment off, its unknowns then map to 0)."""
+    require_l0(cfg)
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -216,6 +220,7 @@ def mass_block(cfg, e, psi_k=None):
     with n = (k_u+1)^3 in an enriched cell whose enrichment is on (psi_k: psi at
     the enriched volume rule), n x n otherwise (psi_k None for a cell without
     enrichment)."""
+    require_l0(cfg)
     pts_e, wts_e = volume_rule(cfg)
     V_e = basis_at(cfg, pts_e)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
@@ -270,6 +275,7 @@ def projection_block(cfg, e, tau_d_e, psi4_k=None):
     layout (components of N_B, then the three enrichment coefficients).
     psi4_k: psi and grad psi at the enriched volume rule, None for a cell
     without enrichment."""
+    require_l0(cfg)
     pts_e, wts_e = volume_rule(cfg)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     M, D, _ = _projection_block(cfg, int(e), psi4_k, tau_d_e, vertex_eta(cfg),
@@ -288,6 +294,7 @@ def projection_step(cfg, u_hat, g, scale, tau_d, psi4, cells=None):
     solved densely.  psi4: [nenr][npts][4] psi and grad psi at the enriched
     volume rule.  cells: optional subset of cells to solve (others stay 0).
     Flat (box) meshes only."""
+    require_l0(cfg)
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3

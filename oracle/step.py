@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import (enriched_cells, enrichment_active, gauss, gauss_lobatto, lagrange, psi_point, psi_volume, psi_volume4,
-               vertex_eta, viscous_multiscale)
+               require_l0, vertex_eta, viscous_multiscale)
 from .project import inverse_mass, mass_apply
 
 
@@ -27,6 +27,7 @@ def helmholtz_solve(cfg, u_nut, tau, gamma, b, rtol=1e-11, x0=None):
     gamma = gamma0/dt, A = -F^nu of eq. viscous_multiscale with nu_t from
     the enrichment of u_nut), by GMRES on the M^{-1}-scaled form
     gamma x + M^{-1} A x = gamma b.  Returns (x, GMRES iterations)."""
+    require_l0(cfg)
     import scipy.sparse.linalg as sla
     psi = _psi(cfg, tau)
     n = cfg.n_vel
@@ -50,6 +51,7 @@ def helmholtz_solve(cfg, u_nut, tau, gamma, b, rtol=1e-11, x0=None):
 
 def helmholtz_residual(cfg, u_nut, tau, gamma, b, x):
     """gamma M x + A x - gamma M b with the forward mass matrix (no inverse)."""
+    require_l0(cfg)
     psi = _psi(cfg, tau)
     u_nut = np.zeros(cfg.n_vel) if u_nut is None else u_nut
     return gamma * mass_apply(cfg, x, psi) + viscous_multiscale(cfg, x, u_nut=u_nut, tau=tau) \
@@ -86,6 +88,7 @@ def vorticity_rhs(cfg, u, tau):
     """b(v) = (v, curl u)_e for every velocity test function (N_B e_c, and
     psi e_c in an enriched cell whose enrichment is on) with the cell's
     velocity rule (nq_u^3, or nq_u x nq_wn x nq_u), u = u_bar + psi u~."""
+    require_l0(cfg)
     from .project import volume_rule
     n3 = (cfg.k_u + 1) ** 3
     u = np.asarray(u, dtype=np.float64)
@@ -116,6 +119,7 @@ def vorticity_rhs(cfg, u, tau):
 def vorticity(cfg, u, tau):
     """omega_h = L2 projection of curl u_h onto the enriched velocity space
     (Sec. 4.2, below eq. ipflux): M omega = vorticity_rhs."""
+    require_l0(cfg)
     return inverse_mass(cfg, vorticity_rhs(cfg, u, tau), _psi(cfg, tau))
 
 
@@ -127,6 +131,7 @@ def pressure_neumann(cfg, us, omegas, betas, f, tau):
     +e_y on the upper one), at the Gauss points of the velocity face rule
     (nq_u x nq_u) against the pressure basis; u_i = u_bar + psi u~ and
     omega_i likewise in enriched cells (psi = 0 on the wall, grad psi not)."""
+    require_l0(cfg)
     if cfg.fully_periodic:
         return np.zeros(cfg.n_p)
     npu, npp = cfg.k_u + 1, cfg.k_p + 1
@@ -182,6 +187,7 @@ def dual_splitting_step(cfg, tau, u_n, u_nm1, dt, order=2, f=(0.0, 0.0, 0.0), dt
     u^n), Helmholtz step (eq. helmholtzspat, nu_t from u^n).  Constant-step
     BDF/extrapolation coefficients of order 1 or 2.  Returns (u^{n+1}, p,
     u_hat, u_hathat)."""
+    require_l0(cfg)
     from . import convective_residual, divdiv_tau, pressure_gradient, velocity_divergence
     from . import solve as osolve
     from .project import projection_step

@@ -51,6 +51,7 @@ class MeshConfig:
     psi_kind: int = 0          # 0: Spalding's law, 1: van Driest's law
     A_plus: float = 26.0
     yplus_off: float = 0.0     # > 0: switch a wall cell's enrichment off while all its points have y+ below this
+    enrich_degree: int = 0     # tensor degree l of the enrichment weights (0: 3, 1: 24 DoFs per enriched cell)
 
     def as_dict(self):
         return asdict(self)
@@ -76,7 +77,12 @@ class MeshConfig:
 
     @property
     def n_vel(self) -> int:
-        return self.ncell * 3 * (self.k_u + 1) ** 3 + 3 * self.n_enriched
+        return self.ncell * 3 * (self.k_u + 1) ** 3 + self.n_enr_dofs
+
+    @property
+    def n_enr_dofs(self) -> int:
+        """Enrichment unknowns: 3 (l+1)^3 per enriched cell."""
+        return 3 * (self.enrich_degree + 1) ** 3 * self.n_enriched
 
     @property
     def n_p(self) -> int:
@@ -128,7 +134,7 @@ def draw_inputs(wl: Workload, want=("u", "tau", "p"), dtype=np.float64):
     out = {}
     npu3 = (m.k_u + 1) ** 3
     u_poly = rng.uniform(-1.0, 1.0, size=m.ncell * 3 * npu3)
-    u_enr = rng.uniform(-1.0, 1.0, size=3 * m.n_enriched)
+    u_enr = rng.uniform(-1.0, 1.0, size=m.n_enr_dofs)
     if wl.tau_lo == wl.tau_hi:
         tau = np.full(m.n_tau, wl.tau_lo)
     else:
