@@ -38,10 +38,14 @@
  *  wall-normal vertices y_j = tanh(gamma (2j/ny - 1))/tanh(gamma) (paper
  *  Sec. 5.1; gamma = 0: uniform).  Reference cell [0,1]^3, nodal tensor basis
  *  through the Gauss-Lobatto points, node B = i + (k+1)(j + (k+1) m).
- *  Velocity vector (paper Sec. 3.1, eqs. space/std_fe/enrichment, l = 0):
+ *  Velocity vector (paper Sec. 3.1, eqs. space/std_fe/enrichment):
  *    [cell][component c=0..2][node B]  followed by the enrichment block
- *    [enriched cell][component], enriched cells being the wall-adjacent layer
- *    of each enriched wall, numbered in increasing cell index.
+ *    [enriched cell][component][enrichment node], enriched cells being the
+ *    wall-adjacent layer of each enriched wall, numbered in increasing cell
+ *    index.  Enrichment weights of degree l = 0 (the paper's runs): one
+ *    enrichment node, 3 unknowns per enriched cell; l = 1: the eight
+ *    trilinear vertex functions N_B = prod_d (b_d ? xi_d : 1 - xi_d),
+ *    node bx + 2 (by + 2 bz), 24 unknowns per enriched cell.
  *  Pressure vector: [cell][node B] with degree k_p.
  *  Wall shear stress (tau_w) per wall-face Gauss point of the velocity rule:
  *    [wall w (0 lower, 1 upper)][ez][ex][qz][qx], nq_u^2 values per face.
@@ -89,6 +93,11 @@ typedef struct {
   double A_plus;          /* van Driest damping constant A+ (paper: 26)                   */
   double yplus_off;       /* > 0: switch-off threshold of the enrichment (paper: 30), see   */
                           /*      dg_update_wall_shear; 0: the enrichment is always on      */
+  int32_t enrich_degree;  /* tensor degree l of the enrichment weights (Sec. 3.1, eq.       */
+                          /*   enrichment): 0 or 1.  l = 1 is built for flat walls and, of  */
+                          /*   the velocity operators, for dg_apply_velocity_residual and   */
+                          /*   dg_apply_convective; every other entry point that reads or   */
+                          /*   writes a velocity vector returns DG_ERR_UNSUPPORTED for it   */
 } dg_mesh_params;
 
 /* Wall laws for psi = U(y+) (paper Sec. 3.2): Spalding's implicit law with

@@ -100,6 +100,9 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
     return set_error(DG_ERR_ARG, "A_plus must be positive and finite");
   if (!(P.yplus_off >= 0) || !std::isfinite(P.yplus_off))
     return set_error(DG_ERR_ARG, "yplus_off must be >= 0 and finite");
+  if (P.enrich_degree != 0 && P.enrich_degree != 1) return set_error(DG_ERR_ARG, "enrich_degree must be 0 or 1");
+  if (P.enrich_degree == 1 && P.wall_amp != 0.0)
+    return set_error(DG_ERR_UNSUPPORTED, "degree-1 enrichment weights are built for flat walls only");
   if (P.wall_amp != 0.0 && P.fully_periodic) return set_error(DG_ERR_ARG, "a curved wall needs walls");
   if (!(std::fabs(P.wall_amp) < 0.9)) return set_error(DG_ERR_ARG, "wall amplitude must be below 0.9");
   m.P = P;
@@ -114,7 +117,8 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
     if (P.enrich_upper) m.upper_slot = m.n_enr_layers++;
   }
   m.nenr = (int64_t)P.nx * P.nz * m.n_enr_layers;
-  m.n_vel = m.ncell * 3 * (int64_t)m.np_u * m.np_u * m.np_u + 3 * m.nenr;
+  m.nle = P.enrich_degree ? 8 : 1;
+  m.n_vel = m.ncell * 3 * (int64_t)m.np_u * m.np_u * m.np_u + 3 * (int64_t)m.nle * m.nenr;
   m.n_p = m.ncell * (int64_t)m.np_p * m.np_p * m.np_p;
   m.n_tau = 2 * (int64_t)P.nz * P.nx * P.nq_u * P.nq_u;
   m.psi_pts = psi_points(P.nq_u, P.nq_wn);
@@ -127,6 +131,9 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
   if (m.nenr > 0 && !velocity_supported(m.np_u, P.nq_u, nqw_eff))
     return set_error(DG_ERR_UNSUPPORTED, std::string("velocity (k_u+1, nq_u, nq_wn) not compiled; have ") +
                                              velocity_combos());
+  if (m.nenr > 0 && m.nle != 1 && !velocity_l1_supported(m.np_u, P.nq_u, P.nq_wn))
+    return set_error(DG_ERR_UNSUPPORTED, std::string("degree-1 enrichment weights: (k_u+1, nq_u, nq_wn) not "
+                                                     "compiled; have ") + velocity_l1_combos());
   if (m.nenr == 0) {
     bool any = false;
     for (int w = 1; w <= kMaxQ && !any; ++w) any = velocity_supported(m.np_u, P.nq_u, w);
@@ -390,6 +397,7 @@ int dg_wall_shear_nodes(const dg_mesh* m, const double* u, double* tau_nodes, vo
   if (!m || !u || !tau_nodes) return set_error(DG_ERR_ARG, "mesh/u/tau_nodes is NULL");
   if (m->curved || m->P.fully_periodic)
     return set_error(DG_ERR_UNSUPPORTED, "nodal wall shear stress: flat no-slip walls only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (static_cast<const void*>(u) == static_cast<const void*>(tau_nodes))
     return set_error(DG_ERR_ARG, "u and tau_nodes must not alias");
   if (!aligned256(u) || !aligned256(tau_nodes)) return set_error(DG_ERR_ARG, "u and tau_nodes must be 256-byte aligned");
@@ -413,6 +421,7 @@ int dg_update_wall_shear_nodes(dg_mesh* m, const double* tau_nodes, void* stream
 int dg_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, void* stream) {
   if (!m || !u_old || !u_new) return set_error(DG_ERR_ARG, "mesh/u_old/u_new is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "projection onto the refreshed space: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!aligned256(u_old) || !aligned256(u_new)) return set_error(DG_ERR_ARG, "u_old and u_new must be 256-byte aligned");
   return launch_project_velocity(m, u_old, u_new, static_cast<hipStream_t>(stream));
 }
@@ -420,6 +429,7 @@ int dg_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, vo
 int dg_apply_inverse_mass(const dg_mesh* m, const double* r, double* x, void* stream) {
   if (!m || !r || !x) return set_error(DG_ERR_ARG, "mesh/r/x is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "inverse mass: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!aligned256(r) || !aligned256(x)) return set_error(DG_ERR_ARG, "r and x must be 256-byte aligned");
   return launch_inverse_mass(m, r, x, static_cast<hipStream_t>(stream));
 }
@@ -427,6 +437,7 @@ int dg_apply_inverse_mass(const dg_mesh* m, const double* r, double* x, void* st
 int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, void* stream) {
   if (!m || !p || !g) return set_error(DG_ERR_ARG, "mesh/p/g is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "pressure gradient: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (static_cast<const void*>(p) == static_cast<const void*>(g)) return set_error(DG_ERR_ARG, "p and g must not alias");
   if (!aligned256(p) || !aligned256(g)) return set_error(DG_ERR_ARG, "p and g must be 256-byte aligned");
   return launch_divgrad(m, false, p, g, static_cast<hipStream_t>(stream));
@@ -435,6 +446,7 @@ int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, voi
 int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, void* stream) {
   if (!m || !u || !c) return set_error(DG_ERR_ARG, "mesh/u/c is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "velocity divergence: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (static_cast<const void*>(u) == static_cast<const void*>(c)) return set_error(DG_ERR_ARG, "u and c must not alias");
   if (!aligned256(u) || !aligned256(c)) return set_error(DG_ERR_ARG, "u and c must be 256-byte aligned");
   return launch_divgrad(m, true, u, c, static_cast<hipStream_t>(stream));
@@ -443,6 +455,7 @@ int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, v
 int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* tau_d, void* stream) {
   if (!m || !u || !tau_d) return set_error(DG_ERR_ARG, "mesh/u/tau_d is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!(dt_over_cr >= 0) || !std::isfinite(dt_over_cr)) return set_error(DG_ERR_ARG, "dt/Cr must be >= 0 and finite");
   if (static_cast<const void*>(u) == static_cast<const void*>(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must not alias");
   if (!aligned256(u) || !aligned256(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must be 256-byte aligned");
@@ -452,6 +465,7 @@ int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* 
 int dg_apply_divdiv(const dg_mesh* m, const double* tau_d, const double* u, double* out, void* stream) {
   if (!m || !tau_d || !u || !out) return set_error(DG_ERR_ARG, "mesh/tau_d/u/out is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (u == out) return set_error(DG_ERR_ARG, "u and out must not alias");
   if (!aligned256(u) || !aligned256(out) || !aligned256(tau_d))
     return set_error(DG_ERR_ARG, "tau_d, u and out must be 256-byte aligned");
@@ -462,6 +476,7 @@ int dg_projection_step(const dg_mesh* m, const double* tau_d, const double* u_ha
                        double* x, void* stream) {
   if (!m || !tau_d || !u_hat || !g || !x) return set_error(DG_ERR_ARG, "mesh/tau_d/u_hat/g/x is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "projection step: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!std::isfinite(scale)) return set_error(DG_ERR_ARG, "scale must be finite");
   if (x == u_hat || x == g || x == tau_d) return set_error(DG_ERR_ARG, "x must not alias u_hat, g or tau_d");
   if (!aligned256(tau_d) || !aligned256(u_hat) || !aligned256(g) || !aligned256(x))
@@ -477,6 +492,7 @@ int64_t dg_eddy_viscosity_points(const dg_mesh* m) {
 int dg_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double beta, double* nut, void* stream) {
   if (!m || !u || !nut) return set_error(DG_ERR_ARG, "mesh/u/nut is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "eddy viscosity: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!(c_des > 0) || !std::isfinite(c_des) || !(beta > 0) || !std::isfinite(beta))
     return set_error(DG_ERR_ARG, "c_des and beta must be positive and finite");
   if (static_cast<const void*>(u) == static_cast<const void*>(nut)) return set_error(DG_ERR_ARG, "u and nut must not alias");
@@ -487,6 +503,7 @@ int dg_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double be
 int dg_apply_viscous_multiscale(const dg_mesh* m, const double* nut, const double* u, double* out, void* stream) {
   if (!m || !u || !out || (!nut && m->nenr > 0)) return set_error(DG_ERR_ARG, "mesh/nut/u/out is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "multiscale viscous operator: flat meshes only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (u == out || (nut && (nut == u || nut == out))) return set_error(DG_ERR_ARG, "u, out and nut must not alias");
   if (!aligned256(u) || !aligned256(out) || (nut && !aligned256(nut)))
     return set_error(DG_ERR_ARG, "nut, u and out must be 256-byte aligned");
@@ -550,6 +567,8 @@ int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, 
     if (!meshes[i] || !u[i] || !r[i]) return set_error(DG_ERR_ARG, "a batch entry has a NULL mesh/u/r");
     if (u[i] == r[i]) return set_error(DG_ERR_ARG, "u and r of a batch entry must not alias");
     if (!aligned256(u[i]) || !aligned256(r[i])) return set_error(DG_ERR_ARG, "u and r must be 256-byte aligned");
+    if (meshes[i]->nle != 1)
+      return set_error(DG_ERR_UNSUPPORTED, "the batched residual is built for l = 0 enrichment weights only");
     for (int j = 0; j < i; ++j)
       if (r[j] == r[i]) return set_error(DG_ERR_ARG, "two batch entries share an output vector");
   }

@@ -136,6 +136,7 @@ struct dg_mesh {
   int64_t ncell, nenr, n_vel, n_p, n_tau;
   int np_u, np_p;
   int n_enr_layers;       // 0, 1 or 2
+  int nle;                // enrichment functions per component and enriched cell: (l+1)^3 = 1 or 8
   int lower_slot, upper_slot;  // enriched-layer slot of each wall or -1
   int psi_pts;            // points per enriched cell in the psi tables
   double hx, hz;
@@ -265,6 +266,8 @@ int launch_velocity_batched(const dg_mesh* const* meshes, int n, dg_prec prec, c
                             void* ws, size_t ws_bytes, hipStream_t s);
 bool poisson_supported(int np, int nq);
 bool velocity_supported(int np, int nq, int nqy);
+bool velocity_l1_supported(int np, int nq, int nqy);  // degree-1 enrichment weights
+const char* velocity_l1_combos();
 const char* velocity_combos();
 const char* poisson_combos();
 

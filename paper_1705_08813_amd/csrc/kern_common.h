@@ -207,4 +207,23 @@ __device__ __forceinline__ void block_sum3(T v[3], T* red /* >= 3 * nwaves */) {
   }
 }
 
+// Workgroup sum of N per-thread values; thread i < N receives sum i in v[0].
+template <int N, typename T>
+__device__ __forceinline__ void block_sum_n(T* v, T* red /* >= N * nwaves */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    T x = v[c];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[N * wave + c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    T s = 0;
+    for (int w = 0; w < nw; ++w) s += red[N * w + threadIdx.x];
+    v[0] = s;
+  }
+}
+
 }  // namespace dgwm

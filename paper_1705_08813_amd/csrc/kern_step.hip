@@ -320,6 +320,7 @@ int dg_vorticity_rhs(const dg_mesh* m, const double* u, double* b, void* stream)
   if (!m || !u || !b) return set_error(DG_ERR_ARG, "mesh/u/b is NULL");
   if (u == b) return set_error(DG_ERR_ARG, "u and b must not alias");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the vorticity is built for flat walls only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   return launch_vorticity_rhs(m, u, b, static_cast<hipStream_t>(stream));
 }
 
@@ -327,6 +328,7 @@ int dg_vorticity(const dg_mesh* m, const double* u, double* omega, void* stream)
   if (!m || !u || !omega) return set_error(DG_ERR_ARG, "mesh/u/omega is NULL");
   if (u == omega) return set_error(DG_ERR_ARG, "u and omega must not alias");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the vorticity is built for flat walls only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   const hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = launch_vorticity_rhs(m, u, omega, s);
   if (!rc) rc = launch_inverse_mass(m, omega, omega, s);
@@ -340,6 +342,7 @@ int dg_pressure_neumann(const dg_mesh* m, int32_t nhist, const double* const* u,
   for (int h = 0; h < nhist; ++h)
     if (!u[h] || !omega[h]) return set_error(DG_ERR_ARG, "a velocity or vorticity vector is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Neumann data is built for flat walls only");
+  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   return launch_pressure_neumann(m, nhist, u, omega, beta, f, rhs, static_cast<hipStream_t>(stream));
 }
 

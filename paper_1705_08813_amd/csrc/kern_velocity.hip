@@ -1,6 +1,8 @@
 // Enriched DG velocity residual (arXiv 1705.08813, Sec. 3.1 and 4.2):
 // local Lax-Friedrichs convective term + interior-penalty viscous term on the
-// space u = u_bar + psi u~ (l = 0 enrichment in the wall-adjacent layer).
+// space u = u_bar + psi sum_B N^l_B u~_B (enrichment in the wall-adjacent
+// layer; weights of degree l = 0, one coefficient per component, or l = 1,
+// the eight trilinear vertex functions of the cell, eq. enrichment).
 //
 // One workgroup per cell.  The cell's nodal values are staged in LDS; values
 // and gradients at the Gauss points come from sum-factorized sweeps (basis
@@ -60,6 +62,44 @@ __device__ __forceinline__ void line_of(int D, int a, int b, int& base, int& str
 }
 
 // Neighbour of the current cell across face (D, S).
+// Degree-1 enrichment weights (Sec. 3.1, eq. enrichment with l = 1): the
+// trilinear vertex functions N_B = prod_d (b_d ? xi_d : 1 - xi_d) of the
+// reference point xi, B = bx + 2 (by + 2 bz), and their physical derivatives
+// on an affine cell (ih: reciprocal cell sizes).
+template <typename T>
+__device__ __forceinline__ void vertex_fns(const T xi[3], const T ih[3], T n[8], T dn[3][8]) {
+  const T v[3][2] = {{T(1) - xi[0], xi[0]}, {T(1) - xi[1], xi[1]}, {T(1) - xi[2], xi[2]}};
+#pragma unroll
+  for (int B = 0; B < 8; ++B) {
+    const int bx = B & 1, by = (B >> 1) & 1, bz = B >> 2;
+    n[B] = v[0][bx] * v[1][by] * v[2][bz];
+    dn[0][B] = (bx ? ih[0] : -ih[0]) * v[1][by] * v[2][bz];
+    dn[1][B] = (by ? ih[1] : -ih[1]) * v[0][bx] * v[2][bz];
+    dn[2][B] = (bz ? ih[2] : -ih[2]) * v[0][bx] * v[1][by];
+  }
+}
+
+// The weight field L_c = sum_B N_B ut[c][B] and its gradient dL[c][d].
+template <typename T>
+__device__ __forceinline__ void vertex_weight(const T* ut, const T n[8], const T dn[3][8], T L[3], T dL[3][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T a = 0, g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+    for (int B = 0; B < 8; ++B) {
+      const T w = ut[c * 8 + B];
+      a += n[B] * w;
+      g0 += dn[0][B] * w;
+      g1 += dn[1][B] * w;
+      g2 += dn[2][B] * w;
+    }
+    L[c] = a;
+    dL[c][0] = g0;
+    dL[c][1] = g1;
+    dL[c][2] = g2;
+  }
+}
+
 struct FaceNb {
   int64_t enb;     // neighbour cell (valid unless wall)
   int64_t enr_nb;  // its enriched index or -1
@@ -93,10 +133,11 @@ template <typename T, int NP>
 struct NbLines {
   static constexpr int NP2 = NP * NP, N = 6 * 3 * NP2, ITEMS = (N + 255) / 256;
   T x[ITEMS][NP];
-  T nut;  // enrichment coefficient of a neighbour (threads 0..17: face f = tid / 3, component tid % 3)
+  T nut;  // enrichment coefficient of a neighbour (threads 0..18 LE - 1: face f = tid / (3 LE),
+          // then [component][enrichment node])
 };
 
-template <typename T, int NP>
+template <typename T, int NP, int LE = 1>
 __device__ __forceinline__ void nb_fetch(const MeshDev& M, const T* __restrict__ u, int ex, int ey, int ez,
                                          NbLines<T, NP>& L) {
   using NL = NbLines<T, NP>;
@@ -120,16 +161,16 @@ __device__ __forceinline__ void nb_fetch(const MeshDev& M, const T* __restrict__
     }
   }
   L.nut = 0;
-  if (threadIdx.x < 18) {
-    const int f = threadIdx.x / 3, c = threadIdx.x % 3;
+  if (threadIdx.x < 18 * LE) {
+    const int f = threadIdx.x / (3 * LE), k = threadIdx.x % (3 * LE);
     const FaceNb nb = face_nb(M, ex, ey, ez, f >> 1, f & 1);
-    if (nb.enr_nb >= 0) L.nut = u[M.enr_off + nb.enr_nb * 3 + c];
+    if (nb.enr_nb >= 0) L.nut = u[M.enr_off + nb.enr_nb * 3 * LE + k];
   }
 }
 
 // ihn: reciprocal size along the face normal of the neighbours across the
 // faces y = 0 and y = 1 of the cell (x and z sizes are uniform)
-template <typename T, int NP, int NQ, bool REF>
+template <typename T, int NP, int NQ, bool REF, int LE = 1>
 __device__ __forceinline__ void nb_store(const MeshDev& M, const NbLines<T, NP>& L, T* s_nl, T* s_nut, int ex, int ey,
                                          int ez, T ihx, T ihz, T ihy0, T ihy1) {
   using NL = NbLines<T, NP>;
@@ -162,7 +203,7 @@ __device__ __forceinline__ void nb_store(const MeshDev& M, const NbLines<T, NP>&
       s_nl[((f * 3 + c) * 2 + 1) * NP2 + k] = der;
     }
   }
-  if (threadIdx.x < 18) s_nut[threadIdx.x] = L.nut;
+  if (threadIdx.x < 18 * LE) s_nut[threadIdx.x] = L.nut;
 }
 
 // 1-D tables used by the face phases, staged in LDS in the working precision
@@ -305,10 +346,11 @@ __device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr
 // Every 1-D contraction runs as a thread-owned line with the table entries
 // as literals of the unrolled code (one LDS read per input, none per
 // coefficient); phases are separated by workgroup barriers.
-template <typename T, int NP, int NQ, int NQY, bool ENR, int D, bool MS = false>
+template <typename T, int NP, int NQ, int NQY, bool ENR, int D, bool MS = false, int LE = 1>
 __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, const T* s_nl, const T* s_nut, T* s_r,
                                               T* s_face, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
-                                              T hy, T hz, T ihx, T ihy, T ihz, T rt[3]) {
+                                              T hy, T hz, T ihx, T ihy, T ihz, T* rt) {
+  static_assert(LE == 1 || (LE == 8 && !MS), "degree-1 weights are built for the velocity residual");
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr int T1 = D == 0 ? 1 : 0;
   constexpr int T2 = D == 2 ? 1 : 2;
@@ -345,6 +387,8 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   const T tau0 = tau_of(nb0), tau1 = tau_of(nb1);
   const bool wall0 = nb0.wall, wall1 = nb1.wall;
   const int64_t enrn0 = nb0.enr_nb, enrn1 = nb1.enr_nb;
+  // neighbours' reciprocal sizes along D (degree-1 weights of an enriched neighbour)
+  const T ihn0 = D == 1 ? T(M.ihy[nb0.nidx1]) : ihd, ihn1 = D == 1 ? T(M.ihy[nb1.nidx1]) : ihd;
 
   // Phase A: own node layers of both faces (value, d/dx_D), one line each
   for (int t = tid; t < 3 * NP2; t += nt) {
@@ -471,19 +515,38 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
       continue;
     }
     T psim = 0, gpsim[3] = {0, 0, 0};
+    // degree-1 weights: vertex functions at the face point (own cell, xi_D = s)
+    T nB[LE], dB[3][LE];
     if (ENR) {
       const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + 2 * D + s] + pt) * 4;
       psim = T(ps[0]);
       gpsim[0] = T(ps[1]);
       gpsim[1] = T(ps[2]);
       gpsim[2] = T(ps[3]);
+      if constexpr (LE == 1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        tr[0][c] += psim * s_ut[c];
-        tr[0][3 + c] += s_ut[c] * gpsim[D];
+        for (int c = 0; c < 3; ++c) {
+          tr[0][c] += psim * s_ut[c];
+          tr[0][3 + c] += s_ut[c] * gpsim[D];
+        }
+        tr[0][6] += s_ut[D] * gpsim[T1];
+        tr[0][7] += s_ut[D] * gpsim[T2];
+      } else {
+        // u~_c = psi L_c:  d_k u~_c = L_c d_k psi + psi d_k L_c
+        T xi[3], L[3], dL[3][3];
+        xi[D] = T(s);
+        xi[T1] = T(tb1.g[q1]);
+        xi[T2] = T(tb2.g[q2]);
+        vertex_fns(xi, ihown, nB, dB);
+        vertex_weight(s_ut, nB, dB, L, dL);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          tr[0][c] += psim * L[c];
+          tr[0][3 + c] += L[c] * gpsim[D] + psim * dL[c][D];
+        }
+        tr[0][6] += L[D] * gpsim[T1] + psim * dL[D][T1];
+        tr[0][7] += L[D] * gpsim[T2] + psim * dL[D][T2];
       }
-      tr[0][6] += s_ut[D] * gpsim[T1];
-      tr[0][7] += s_ut[D] * gpsim[T2];
     }
     if (wall) {
 #pragma unroll
@@ -492,14 +555,32 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
       const double* ps = M.psi + ((size_t)enr_nb * M.psi_pts + M.psi_off[1 + 2 * D + (1 - s)] + pt) * 4;
       const T psip = T(ps[0]);
       const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
-      const T* ut = s_nut + (2 * D + s) * 3;
+      const T* ut = s_nut + (2 * D + s) * 3 * LE;
+      if constexpr (LE == 1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        tr[1][c] += psip * ut[c];
-        tr[1][3 + c] += ut[c] * gpp[D];
+        for (int c = 0; c < 3; ++c) {
+          tr[1][c] += psip * ut[c];
+          tr[1][3 + c] += ut[c] * gpp[D];
+        }
+        tr[1][6] += ut[D] * gpp[T1];
+        tr[1][7] += ut[D] * gpp[T2];
+      } else {
+        // the neighbour's vertex functions at the same point (its xi_D = 1 - s)
+        T xin[3], ihn[3] = {ihown[0], ihown[1], ihown[2]}, nn[8], dn[3][8], L[3], dL[3][3];
+        xin[D] = T(1 - s);
+        xin[T1] = T(tb1.g[q1]);
+        xin[T2] = T(tb2.g[q2]);
+        ihn[D] = s ? ihn1 : ihn0;
+        vertex_fns(xin, ihn, nn, dn);
+        vertex_weight(ut, nn, dn, L, dL);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          tr[1][c] += psip * L[c];
+          tr[1][3 + c] += L[c] * gpp[D] + psip * dL[c][D];
+        }
+        tr[1][6] += L[D] * gpp[T1] + psip * dL[D][T1];
+        tr[1][7] += L[D] * gpp[T2] + psip * dL[D][T2];
       }
-      tr[1][6] += ut[D] * gpp[T1];
-      tr[1][7] += ut[D] * gpp[T2];
     }
     // n = sg e_D
     const T unm = sg * tr[0][D], unp = sg * tr[1][D];
@@ -528,13 +609,25 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
       const T Fn = (c == D) ? -T(2) * hth * jmp[D] : -hth * jmp[c];
       fo[c * FP] = wf * fv;
       fo[(3 + c) * FP] = wf * Fn;
-      if (ENR) rt[c] += wf * (psim * fv + Fn * gpsim[D]);
+      if constexpr (ENR && LE == 1) rt[c] += wf * (psim * fv + Fn * gpsim[D]);
+      if constexpr (ENR && LE == 8) {
+        // test functions psi N_B e_c: value psi N_B, d_D (psi N_B) = N_B d_D psi + psi d_D N_B
+#pragma unroll
+        for (int B = 0; B < 8; ++B)
+          rt[c * 8 + B] += wf * (psim * nB[B] * fv + Fn * (nB[B] * gpsim[D] + psim * dB[D][B]));
+      }
     }
     // F_g[D][T1] = -theta nu/2 jmp_T1 sg,  F_g[D][T2] = -theta nu/2 jmp_T2 sg
     const T Ft1 = -hth * jmp[T1], Ft2 = -hth * jmp[T2];
     fo[6 * FP] = wf * Ft1;
     fo[7 * FP] = wf * Ft2;
-    if (ENR) rt[D] += wf * (Ft1 * gpsim[T1] + Ft2 * gpsim[T2]);
+    if constexpr (ENR && LE == 1) rt[D] += wf * (Ft1 * gpsim[T1] + Ft2 * gpsim[T2]);
+    if constexpr (ENR && LE == 8) {
+#pragma unroll
+      for (int B = 0; B < 8; ++B)
+        rt[D * 8 + B] += wf * (Ft1 * (nB[B] * gpsim[T1] + psim * dB[T1][B]) +
+                               Ft2 * (nB[B] * gpsim[T2] + psim * dB[T2][B]));
+    }
   }
   __syncthreads();
 
@@ -1402,17 +1495,18 @@ __device__ __forceinline__ void vel_cell_affine(const MeshDev& M, const T* __res
 
 // One cell: block-local index b within its launch (regular cells: layer range
 // [layer_lo, layer_lo + nlayers); enriched cells: the enriched index).
-template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED, bool MS = false>
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED, bool MS = false, int LE = 1>
 __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
                                                  int layer_lo, int nlayers) {
+  static_assert(LE == 1 || (LE == 8 && !CURVED && !MS), "degree-1 weights: flat cells, velocity residual");
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr int NP3 = Sh::NP3, NPTS = Sh::NPTS;
   __shared__ T s_u[3 * NP3];
   __shared__ T s_r[3 * NP3];
   __shared__ T s_big[Sh::BIG];
-  __shared__ T s_ut[3];
-  __shared__ T s_nut[18];
-  __shared__ T s_red[3 * 4];
+  __shared__ T s_ut[3 * LE];      // enrichment coefficients [c][B]
+  __shared__ T s_nut[18 * LE];    // the neighbours' ones [face][c][B]
+  __shared__ T s_red[3 * LE * 4];
   __shared__ T s_tab[FaceTab<NP, NQ, NQY>::size];
   const int tid = threadIdx.x;
   constexpr int nt = 256;  // workgroup size of every velocity launch
@@ -1453,9 +1547,9 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
   const double* mDy = tab + (ENR ? TL.Dy : TL.D);
 
   for (int i = tid; i < 3 * NP3; i += nt) s_u[i] = u[e * 3 * NP3 + i];
-  if (ENR && tid < 3) s_ut[tid] = u[M.enr_off + enr * 3 + tid];
+  if (ENR && tid < 3 * LE) s_ut[tid] = u[M.enr_off + enr * 3 * LE + tid];
   NbLines<T, NP> nbl;
-  nb_fetch<T, NP>(M, u, ex, ey, ez, nbl);
+  nb_fetch<T, NP, LE>(M, u, ex, ey, ez, nbl);
   if (CURVED) load_face_tab<T, NP, NQ, NQY, ENR>(tab, s_tab);
   __syncthreads();
 
@@ -1484,7 +1578,9 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
   __syncthreads();
 
   // pointwise flux G = 2 nu eps(u) - u (x) u, times the quadrature weight
-  T rt[3] = {0, 0, 0};
+  T rt[3 * LE];
+#pragma unroll
+  for (int i = 0; i < 3 * LE; ++i) rt[i] = 0;
   const T nu = T(M.nu);
   const T vol = hx * hy * hz;
   for (int pt = tid; pt < NPTS; pt += nt) {
@@ -1545,18 +1641,32 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
       }
       continue;
     }
-    T gps[3] = {0, 0, 0};
+    T gps[3] = {0, 0, 0}, psv = 0;
+    T nB[LE], dB[3][LE];  // degree-1 weights: vertex functions at the point
     if (ENR) {
       const double* ps = M.psi + ((size_t)enr * M.psi_pts + pt) * 4;
-      const T psv = T(ps[0]);
+      psv = T(ps[0]);
       gps[0] = T(ps[1]);
       gps[1] = T(ps[2]);
       gps[2] = T(ps[3]);
+      if constexpr (LE == 1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        uu[c] += psv * s_ut[c];
+        for (int c = 0; c < 3; ++c) {
+          uu[c] += psv * s_ut[c];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) gg[c][d] += s_ut[c] * gps[d];
+          for (int d = 0; d < 3; ++d) gg[c][d] += s_ut[c] * gps[d];
+        }
+      } else {
+        const T xi[3] = {T(tbx.g[qx]), T(tby.g[qy]), T(tbx.g[qz])}, ih3[3] = {ix, iy, iz};
+        T L[3], dL[3][3];
+        vertex_fns(xi, ih3, nB, dB);
+        vertex_weight(s_ut, nB, dB, L, dL);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          uu[c] += psv * L[c];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) gg[c][d] += L[c] * gps[d] + psv * dL[c][d];
+        }
       }
     }
 #pragma unroll
@@ -1565,7 +1675,14 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         G[d] = wq * (nu * (gg[c][d] + gg[d][c]) - uu[c] * uu[d]);
-        if (ENR) rt[c] += G[d] * gps[d];
+        if (ENR && LE == 1) rt[c] += G[d] * gps[d];
+      }
+      if constexpr (ENR && LE == 8) {
+        // grad (psi N_B) = N_B grad psi + psi grad N_B
+        const T a = G[0] * gps[0] + G[1] * gps[1] + G[2] * gps[2];
+#pragma unroll
+        for (int B = 0; B < 8; ++B)
+          rt[c * 8 + B] += nB[B] * a + psv * (G[0] * dB[0][B] + G[1] * dB[1][B] + G[2] * dB[2][B]);
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -1623,32 +1740,36 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
   {
     // neighbours across y = 0 and y = 1 (wrapped; unused on walls)
     const int y0 = ey == 0 ? M.ny - 1 : ey - 1, y1 = ey + 1 == M.ny ? 0 : ey + 1;
-    nb_store<T, NP, NQ, CURVED>(M, nbl, s_nl, s_nut, ex, ey, ez, ix, iz, T(M.ihy[y0]), T(M.ihy[y1]));
+    nb_store<T, NP, NQ, CURVED, LE>(M, nbl, s_nl, s_nut, ex, ey, ez, ix, iz, T(M.ihy[y0]), T(M.ihy[y1]));
   }
   __syncthreads();
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 0>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 0, MS>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 0, MS, LE>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
                                            iz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 1>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 1, MS>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 1, MS, LE>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
                                            iz, rt);
   if (CURVED)
     vel_faces_dir_curved<T, NP, NQ, NQY, ENR, 2>(M, e, s_u, s_nl, s_nut, s_r, s_face, s_ut, s_tab, ex, ey, ez, enr,
                                                  rt);
   else
-    vel_faces_dir<T, NP, NQ, NQY, ENR, 2, MS>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
+    vel_faces_dir<T, NP, NQ, NQY, ENR, 2, MS, LE>(M, s_u, s_nl, s_nut, s_r, s_face, s_ut, ex, ey, ez, enr, hx, hy, hz, ix, iy,
                                            iz, rt);
 
   for (int i = tid; i < 3 * NP3; i += nt) r[e * 3 * NP3 + i] = s_r[i];
-  if (ENR) {
+  if constexpr (ENR && LE == 1) {
     block_sum3(rt, s_red);
     if (tid < 3) r[M.enr_off + enr * 3 + tid] = rt[0];
+  }
+  if constexpr (ENR && LE != 1) {
+    block_sum_n<3 * LE>(rt, s_red);
+    if (tid < 3 * LE) r[M.enr_off + enr * 3 * LE + tid] = rt[0];
   }
 }
 
@@ -1660,9 +1781,10 @@ __host__ __device__ constexpr bool vel_use_affine() { return sizeof(T) == 4; }
 // limited by its LDS, the general path by registers.
 // (FP64 enriched cells keep up to 256 registers, other FP64 cells 168, FP32
 // cells 128: below that they spill.)
-template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED, int LE = 1>
 __host__ __device__ constexpr int vel_wg_per_cu() {
   if (CURVED) return 2;
+  if (LE != 1) return ENR ? 2 : 3;  // general path; enriched cells hold 24 test-row sums
   if (!vel_use_affine<T>() || !AffShape<T, NP, NQ, NQY>::fits) return 3;
   const int by_lds = (160 * 1024) / AffShape<T, NP, NQ, NQY>::BYTES;
   const int by_regs = sizeof(T) == 8 ? (ENR ? 2 : 3) : 4;
@@ -1674,24 +1796,25 @@ __host__ __device__ constexpr int vel_wg_per_cu() {
 // 8-byte LDS value per FMA in its extrapolations and lost to the general
 // path's line-owned face phases (1516 us against 1430 us), so FP64, curved
 // cells and the largest degrees take the general path.
-template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
+// (degree-1 enrichment weights, LE = 8, always take the general path)
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED, int LE = 1>
 __device__ __forceinline__ void vel_cell(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
                                          int layer_lo, int nlayers) {
-  if constexpr (!CURVED && vel_use_affine<T>() && AffShape<T, NP, NQ, NQY>::fits)
+  if constexpr (!CURVED && LE == 1 && vel_use_affine<T>() && AffShape<T, NP, NQ, NQY>::fits)
     vel_cell_affine<T, NP, NQ, NQY, ENR>(M, u, r, b, layer_lo, nlayers);
   else
-    vel_cell_general<T, NP, NQ, NQY, ENR, CURVED>(M, u, r, b, layer_lo, nlayers);
+    vel_cell_general<T, NP, NQ, NQY, ENR, CURVED, false, LE>(M, u, r, b, layer_lo, nlayers);
 }
 
-template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED>
-__global__ __launch_bounds__(256, (vel_wg_per_cu<T, NP, NQ, NQY, ENR, CURVED>())) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
+template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED, int LE = 1>
+__global__ __launch_bounds__(256, (vel_wg_per_cu<T, NP, NQ, NQY, ENR, CURVED, LE>())) void vel_kernel(const MeshDev M, const T* __restrict__ u, T* __restrict__ r,
                                                   int layer_lo, int nlayers) {
   // contiguous cell ranges per XCD (workgroups are dealt round-robin over
   // the 8 XCDs), so neighbouring cells share an L2
   const int nb = gridDim.x, bid = blockIdx.x;
   const int q8 = nb >> 3, r8 = nb & 7, xcd = bid & 7, m8 = bid >> 3;
   const int blk = xcd * q8 + (xcd < r8 ? xcd : r8) + m8;
-  vel_cell<T, NP, NQ, NQY, ENR, CURVED>(M, u, r, blk, layer_lo, nlayers);
+  vel_cell<T, NP, NQ, NQY, ENR, CURVED, LE>(M, u, r, blk, layer_lo, nlayers);
 }
 
 }  // namespace
@@ -1761,6 +1884,25 @@ int launch_vel_t(const dg_mesh* m, const MeshDev& M, const void* u, void* r, hip
   return check_hip(hipGetLastError(), "velocity kernel launch");
 }
 
+// Degree-1 enrichment weights (flat meshes): the regular cells' kernel reads
+// the neighbours' 24 coefficients across the interface faces.
+template <typename T, int NP, int NQ, int NQW>
+int launch_vel_l1_t(const dg_mesh* m, const MeshDev& M, const void* u, void* r, hipStream_t s) {
+  const T* uu = static_cast<const T*>(u);
+  T* rr = static_cast<T*>(r);
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  if (nl > 0) {
+    const unsigned nb = (unsigned)((int64_t)m->P.nx * nl * m->P.nz);
+    hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQ, false, false, 8>), dim3(nb), dim3(256), 0, s, M, uu, rr, lo, nl);
+  }
+  if (m->nenr > 0)
+    hipLaunchKernelGGL((vel_kernel<T, NP, NQ, NQW, true, false, 8>), dim3((unsigned)m->nenr), dim3(256), 0, s, M, uu,
+                       rr, 0, 0);
+  return check_hip(hipGetLastError(), "velocity kernel launch");
+}
+
 MeshDev make_meshdev_u(const dg_mesh* m) {
   MeshDev M{};
   M.nx = m->P.nx;
@@ -1805,6 +1947,13 @@ MeshDev make_meshdev_u(const dg_mesh* m) {
   X(5, 7, 8)             \
   X(6, 8, 8)
 
+// (np, nq, nq_wn) combinations compiled in for degree-1 enrichment weights.
+#define DG_VEL_L1_COMBOS(X) \
+  X(3, 4, 8)                \
+  X(4, 4, 8)                \
+  X(4, 5, 8)                \
+  X(5, 7, 8)
+
 // Regular-layer range of a mesh (cells not in an enriched layer).
 static void regular_layers(const dg_mesh* m, int& lo, int& nl) {
   lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
@@ -1834,6 +1983,16 @@ bool velocity_supported(int np, int nq, int nqy) {
 
 const char* velocity_combos() { return "velocity (k+1, nq_u, nq_wn): (3,4,8) (3,4,4) (4,4,8) (4,5,8) (4,5,5) (5,7,8) (6,8,8)"; }
 
+bool velocity_l1_supported(int np, int nq, int nqy) {
+#define X(a, b, c) \
+  if (np == a && nq == b && nqy == c) return true;
+  DG_VEL_L1_COMBOS(X)
+#undef X
+  return false;
+}
+
+const char* velocity_l1_combos() { return "(3,4,8) (4,4,8) (4,5,8) (5,7,8)"; }
+
 template <int NP, int NQ, int NQW>
 static int launch_visc_ms_t(const dg_mesh* m, MeshDev M, const double* u, double* r, hipStream_t s) {
   const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
@@ -1862,6 +2021,17 @@ int launch_velocity(const dg_mesh* m, dg_prec prec, const void* u, void* r, hipS
   MeshDev M = make_meshdev_u(m);
   if (convective_only) M.nu = 0.0;  // every viscous term carries a factor nu
   const int np = m->np_u, nq = m->P.nq_u, nqw = m->P.nq_wn;
+  if (m->nle != 1 && m->nenr > 0) {
+#define X(a, b, c)                                                                 \
+  if (np == a && nq == b && nqw == c) {                                            \
+    return prec == DG_F64 ? launch_vel_l1_t<double, a, b, c>(m, M, u, r, s)        \
+                          : launch_vel_l1_t<float, a, b, c>(m, M, u, r, s);        \
+  }
+    DG_VEL_L1_COMBOS(X)
+#undef X
+    return set_error(DG_ERR_UNSUPPORTED, std::string("degree-1 enrichment weights: (k_u+1, nq_u, nq_wn) not "
+                                                     "compiled; have ") + velocity_l1_combos());
+  }
   // without enriched cells only the regular kernel runs: nq_wn is irrelevant
 #define X(a, b, c)                                                                 \
   if (np == a && nq == b && (nqw == c || m->nenr == 0)) {                          \
