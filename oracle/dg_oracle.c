@@ -1495,12 +1495,12 @@ int orc_cell_map(const orc_params *P, int64_t e, const double *xi, double *X, do
  * mixing length l_mix = kappa y_DES (1 - exp(-y+/A+)) (eq. lmix), the smooth
  * DES limit y_DES = (y^-beta + (C_DES h)^-beta)^(-1/beta) (eq. ydes; written
  * as y C h / (y^beta + (C h)^beta)^(1/beta), which is 0 at the wall), and
- * h = dy_e / (k+1) the wall-normal cell width over k+1.  u~ = psi ut (l = 0:
- * ut the cell's three enrichment coefficients), so grad u~ = ut (x) grad psi.
+ * h = dy_e / (k+1) the wall-normal cell width over k+1.  gt = grad u~ [c][d]
+ * (u~ = psi sum_B N^l_B ut_B, so grad u~ = sum_B ut_B (x) grad(psi N^l_B)).
  * y = y_h (the wall distance of Sec. 3.2), y+ = y_h sqrt(tau_w)/nu.
  * out: nu_t, y, y+, |eps(u~)|.  Flat walls only. */
-static void eddy_point(const ctx *C, int64_t e, const double xi[3], const double Ji[3][3], const double ut[3],
-                       const psi_pt *ps, double c_des, double beta, double out[4]) {
+static void eddy_point(const ctx *C, int64_t e, const double xi[3], const double Ji[3][3], const double gt[3][3],
+                       double c_des, double beta, double out[4]) {
   int ex, ey, ez;
   cell_index(C, e, &ex, &ey, &ez);
   double yh, gyh[3], tw, gtw[3];
@@ -1513,7 +1513,7 @@ static void eddy_point(const ctx *C, int64_t e, const double xi[3], const double
   double eps2 = 0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
-      double eij = 0.5 * (ut[i] * ps->g[j] + ut[j] * ps->g[i]);
+      double eij = 0.5 * (gt[i][j] + gt[j][i]);
       eps2 += eij * eij;
     }
   double em = sqrt(2.0 * eps2);
@@ -1525,11 +1525,25 @@ static void eddy_point(const ctx *C, int64_t e, const double xi[3], const double
 
 typedef struct {
   double ub[3], gb[3][3];  /* polynomial part u_bar and its gradient [c][d]     */
-  double ut[3], gt[3][3];  /* enrichment part u~ = psi ut and its gradient        */
-  double psi, gpsi[3];     /* psi and grad psi (zero outside enriched cells)      */
+  double ut[3], gt[3][3];  /* enrichment part u~ and its gradient                 */
+  double ev[8], eg[8][3];  /* enrichment functions psi N^l_B and their gradients  */
   double nut;              /* eddy viscosity (zero outside enriched cells)        */
   int enriched;
 } ms_pt;
+
+/* sum_B w_B f_B (x) grad: value and gradient of an enrichment field with
+ * coefficients w[c][B] at a point with enrichment functions ev, eg. */
+static void enr_field(int nle, const double *w, const double *ev, const double (*eg)[3], double v[3],
+                      double g[3][3]) {
+  for (int c = 0; c < 3; ++c) {
+    v[c] = 0;
+    for (int d = 0; d < 3; ++d) g[c][d] = 0;
+    for (int B = 0; B < nle; ++B) {
+      v[c] += ev[B] * w[c * nle + B];
+      for (int d = 0; d < 3; ++d) g[c][d] += eg[B][d] * w[c * nle + B];
+    }
+  }
+}
 
 /* Both scales of the velocity at xi of cell e, and nu_t from the enrichment
  * coefficients of unut. */
@@ -1551,29 +1565,30 @@ static void eval_ms(const ctx *C, const double *u, const double *unut, int64_t e
     o->ut[c] = 0;
     for (int d = 0; d < 3; ++d) o->gt[c][d] = 0;
   }
-  o->psi = 0;
-  o->gpsi[0] = o->gpsi[1] = o->gpsi[2] = 0;
+  for (int B = 0; B < 8; ++B) {
+    o->ev[B] = 0;
+    for (int d = 0; d < 3; ++d) o->eg[B][d] = 0;
+  }
   o->nut = 0;
   o->enriched = (C->enr[e] >= 0);
   if (!o->enriched) return;
   psi_pt ps;
   eval_psi(C, e, xi, Ji, &ps);
-  o->psi = ps.psi;
-  for (int d = 0; d < 3; ++d) o->gpsi[d] = ps.g[d];
-  const double *ut = u + C->ncell * 3 * np3 + C->enr[e] * 3;
-  const double *un = unut + C->ncell * 3 * np3 + C->enr[e] * 3;
-  for (int c = 0; c < 3; ++c) {
-    o->ut[c] = ps.psi * ut[c];
-    for (int d = 0; d < 3; ++d) o->gt[c][d] = ut[c] * ps.g[d];
-  }
-  double ev[4];
-  eddy_point(C, e, xi, Ji, un, &ps, c_des, beta, ev);
-  o->nut = ev[0];
+  enr_basis(C, xi, Ji, &ps, o->ev, o->eg);
+  const int nle = C->nle;
+  const double *ut = u + C->ncell * 3 * np3 + C->enr[e] * 3 * nle;
+  const double *un = unut + C->ncell * 3 * np3 + C->enr[e] * 3 * nle;
+  enr_field(nle, ut, o->ev, (const double(*)[3])o->eg, o->ut, o->gt);
+  double vn[3], gn[3][3], out[4];
+  enr_field(nle, un, o->ev, (const double(*)[3])o->eg, vn, gn);
+  eddy_point(C, e, xi, Ji, (const double(*)[3])gn, c_des, beta, out);
+  o->nut = out[0];
 }
 
 /* A(v, u) = -F^nu_e(v_bar, v~, u_bar, u~) of eq. viscous_multiscale for every
- * test function v of cell e (v_bar = N_B e_c; v~ = psi e_c in an enriched
- * cell), with F^a(w) = 2 a eps(w) and, as the paper's rows and columns read:
+ * test function v of cell e (v_bar = N_B e_c; v~ = psi N^l_B e_c in an
+ * enriched cell), with F^a(w) = 2 a eps(w) and, as the paper's rows and
+ * columns read:
  *   volume:  (eps(v_bar), F^nu(u_bar))_e + (eps(v_bar), F^nuhat(u~))_e
  *            + (eps(v~), F^{nu+nu_t}(u~))_e,
  *            nuhat = min(nu + nu_t, 2 sqrt(nu (nu + nu_t))) (eq. minvt; clip = 0
@@ -1627,12 +1642,13 @@ static void visc_ms_cell(const ctx *C, const double *u, const double *unut, int6
               G[d] = nu * (p.gb[c][d] + p.gb[d][c]) + nhat * (p.gt[c][d] + p.gt[d][c]);
             double *rc = re + c * np3;
             for (int B = 0; B < np3; ++B) rc[B] += wq * (bg[B][0] * G[0] + bg[B][1] * G[1] + bg[B][2] * G[2]);
-            if (p.enriched) {
-              /* eps(psi e_c) : F = sum_d d_d psi F[c][d] for symmetric F */
-              double s = 0;
-              for (int d = 0; d < 3; ++d) s += p.gpsi[d] * nt * (p.gt[c][d] + p.gt[d][c]);
-              rt[c] += wq * s;
-            }
+            if (p.enriched)
+              for (int B = 0; B < nle; ++B) {
+                /* eps(phi e_c) : F = sum_d d_d phi F[c][d] for symmetric F, phi = psi N^l_B */
+                double s = 0;
+                for (int d = 0; d < 3; ++d) s += p.eg[B][d] * nt * (p.gt[c][d] + p.gt[d][c]);
+                rt[c * nle + B] += wq * s;
+              }
           }
         }
   }
@@ -1706,24 +1722,26 @@ static void visc_ms_cell(const ctx *C, const double *u, const double *unut, int6
           for (int B = 0; B < np3; ++B)
             rc[B] += wf * (bv[B] * fv + bg[B][0] * Fg[0] + bg[B][1] * Fg[1] + bg[B][2] * Fg[2]);
         }
-        /* test functions psi e_c */
-        if (e_enr) {
-          double gn = pm.gpsi[0] * nv[0] + pm.gpsi[1] * nv[1] + pm.gpsi[2] * nv[2];
-          double jg = ju[0] * pm.gpsi[0] + ju[1] * pm.gpsi[1] + ju[2] * pm.gpsi[2];
-          for (int c = 0; c < 3; ++c) {
-            double val;
-            if (inner)
-              val = pm.psi * (-Et[c] + tauF * nu * ju[c]) + wm * (nu + pm.nut) * (ju[c] * gn + jg * nv[c]);
-            else /* interface */
-              val = pm.psi * (-Eb[c] + tauF * nu * ju[c]);
-            rt[c] += wf * val;
+        /* test functions phi e_c, phi = psi N^l_B */
+        if (e_enr)
+          for (int B = 0; B < nle; ++B) {
+            const double *gp = pm.eg[B];
+            double gn = gp[0] * nv[0] + gp[1] * nv[1] + gp[2] * nv[2];
+            double jg = ju[0] * gp[0] + ju[1] * gp[1] + ju[2] * gp[2];
+            for (int c = 0; c < 3; ++c) {
+              double val;
+              if (inner)
+                val = pm.ev[B] * (-Et[c] + tauF * nu * ju[c]) + wm * (nu + pm.nut) * (ju[c] * gn + jg * nv[c]);
+              else /* interface */
+                val = pm.ev[B] * (-Eb[c] + tauF * nu * ju[c]);
+              rt[c * nle + B] += wf * val;
+            }
           }
-        }
       }
   }
   if (e_enr) {
-    double *ro = r + C->ncell * 3 * np3 + C->enr[e] * 3;
-    for (int c = 0; c < 3; ++c) ro[c] = rt[c];
+    double *ro = r + C->ncell * 3 * np3 + C->enr[e] * 3 * nle;
+    for (int i = 0; i < 3 * nle; ++i) ro[i] = rt[i];
   }
 }
 
@@ -1731,7 +1749,7 @@ int orc_viscous_multiscale(const orc_params *P, const double *u, const double *u
                            const double *tau_nodes, double c_des, double beta, int clip, const int64_t *cells,
                            int64_t ncells, double *r) {
   ctx C;
-  if (ctx_init_l0(&C, P, tau_w)) return -1;
+  if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   if (P->wall_amp != 0.0) { ctx_free(&C); return -4; }
@@ -1761,7 +1779,7 @@ int orc_viscous_multiscale(const orc_params *P, const double *u, const double *u
 int orc_eddy_viscosity_point(const orc_params *P, const double *u_nut, const double *tau_w, const double *tau_nodes,
                              double c_des, double beta, int64_t e, const double *xi, double *out4) {
   ctx C;
-  if (ctx_init_l0(&C, P, tau_w)) return -1;
+  if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (e < 0 || e >= C.ncell || C.enr[e] < 0 || P->wall_amp != 0.0) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
@@ -1771,7 +1789,10 @@ int orc_eddy_viscosity_point(const orc_params *P, const double *u_nut, const dou
   psi_pt ps;
   eval_psi(&C, e, xi, Ji, &ps);
   int np3 = C.npu * C.npu * C.npu;
-  eddy_point(&C, e, xi, Ji, u_nut + C.ncell * 3 * np3 + C.enr[e] * 3, &ps, c_des, beta, out4);
+  double ev[8], eg[8][3], vn[3], gn[3][3];
+  enr_basis(&C, xi, Ji, &ps, ev, eg);
+  enr_field(C.nle, u_nut + C.ncell * 3 * np3 + C.enr[e] * 3 * C.nle, ev, (const double(*)[3])eg, vn, gn);
+  eddy_point(&C, e, xi, Ji, (const double(*)[3])gn, c_des, beta, out4);
   ctx_free(&C);
   return 0;
 }

@@ -138,8 +138,9 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     switched off, its unknowns set to 0).  cells: the cells to invert (the
     operator is block diagonal; the others are left at 0).  With return_cond,
     also the 2-norm condition number of each cell's block (0 for cells not
-    inverted).  Flat (box) meshes only."""
-    require_l0(cfg)
+    inverted).  Flat (box) meshes only.  With degree-1 enrichment weights
+    (Sec. 3.1 eq. enrichment, l = 1) the enrichment functions of a cell are
+    psi N_B, N_B its eight trilinear vertex functions."""
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -154,15 +155,17 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     V_r = basis_at(cfg, pts_r)
     M_reg = V_r.T @ (wts_r[:, None] * V_r)
     conds = np.zeros(cfg.ncell)
+    nle = _nle(cfg)
     for e in (range(cfg.ncell) if cells is None else [int(c) for c in cells]):
         k = enr.get(e)
-        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e)
+        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e, pts_e)
         conds[e] = np.linalg.cond(M)
         for c in range(3):
             rp = r[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
-            if k is not None and M.shape[0] == n3 + 1:
-                sol = np.linalg.solve(M, np.concatenate([rp, [r[off + 3 * k + c]]]))
-                x[off + 3 * k + c] = sol[n3]
+            if k is not None and M.shape[0] == n3 + nle:
+                o = off + (3 * k + c) * nle
+                sol = np.linalg.solve(M, np.concatenate([rp, r[o:o + nle]]))
+                x[o:o + nle] = sol[n3:]
                 x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = sol[:n3]
             else:
                 x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = np.linalg.solve(M, rp)
@@ -173,7 +176,6 @@ def mass_apply(cfg, x, psi):
     """y = M x with the velocity mass matrix of every cell (the forward
     operator that inverse_mass inverts; same blocks, same psi convention:
     zero rows switch a cell's enrichment off, its unknowns then map to 0)."""
-    require_l0(cfg)
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -187,23 +189,40 @@ def mass_apply(cfg, x, psi):
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     V_r = basis_at(cfg, pts_r)
     M_reg = V_r.T @ (wts_r[:, None] * V_r)
+    nle = _nle(cfg)
     for e in range(cfg.ncell):
         k = enr.get(e)
-        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e)
+        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e, pts_e)
         for c in range(3):
             xp = x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
-            if k is not None and M.shape[0] == n3 + 1:
-                v = M @ np.concatenate([xp, [x[off + 3 * k + c]]])
+            if k is not None and M.shape[0] == n3 + nle:
+                o = off + (3 * k + c) * nle
+                v = M @ np.concatenate([xp, x[o:o + nle]])
                 y[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = v[:n3]
-                y[off + 3 * k + c] = v[n3]
+                y[o:o + nle] = v[n3:]
             else:
                 y[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = M @ xp
     return y
 
 
-def _mass_block(cfg, e, psi_k, eta, M_reg, V_e, wts_e):
-    """Per-component mass matrix of cell e over its local basis (N_B, plus psi
-    while an enriched cell's enrichment is on), the cell's own rule."""
+def _nle(cfg):
+    """Enrichment functions per component and enriched cell: (l+1)^3."""
+    return (getattr(cfg, "enrich_degree", 0) + 1) ** 3
+
+
+def _vertex_fns(pts):
+    """Trilinear vertex functions N_B (B = bx + 2 (by + 2 bz)) at reference points: (npts, 8)."""
+    N = np.ones((len(pts), 8))
+    for B in range(8):
+        for d in range(3):
+            N[:, B] *= pts[:, d] if (B >> d) & 1 else 1.0 - pts[:, d]
+    return N
+
+
+def _mass_block(cfg, e, psi_k, eta, M_reg, V_e, wts_e, pts_e=None):
+    """Per-component mass matrix of cell e over its local basis (N_B, plus the
+    enrichment functions psi N^l_B while an enriched cell's enrichment is on),
+    the cell's own rule."""
     hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
     ey = (e // cfg.nx) % cfg.ny
     detJ = hx * (eta[ey + 1] - eta[ey]) * hz
@@ -211,7 +230,11 @@ def _mass_block(cfg, e, psi_k, eta, M_reg, V_e, wts_e):
         return detJ * M_reg
     ps = np.asarray(psi_k, dtype=float)
     on = bool(np.any(ps != 0.0))
-    Phi = np.hstack([V_e, ps[:, None]]) if on else V_e
+    if _nle(cfg) == 1:
+        E = ps[:, None]
+    else:
+        E = ps[:, None] * _vertex_fns(volume_rule(cfg)[0] if pts_e is None else pts_e)
+    Phi = np.hstack([V_e, E]) if on else V_e
     return Phi.T @ ((detJ * wts_e)[:, None] * Phi)
 
 
@@ -220,13 +243,12 @@ def mass_block(cfg, e, psi_k=None):
     with n = (k_u+1)^3 in an enriched cell whose enrichment is on (psi_k: psi at
     the enriched volume rule), n x n otherwise (psi_k None for a cell without
     enrichment)."""
-    require_l0(cfg)
     pts_e, wts_e = volume_rule(cfg)
     V_e = basis_at(cfg, pts_e)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     V_r = basis_at(cfg, pts_r)
     M_reg = V_r.T @ (wts_r[:, None] * V_r)
-    return _mass_block(cfg, int(e), psi_k, vertex_eta(cfg), M_reg, V_e, wts_e)
+    return _mass_block(cfg, int(e), psi_k, vertex_eta(cfg), M_reg, V_e, wts_e, pts_e)
 
 
 def _basis_grad_at(cfg, pts, h):

@@ -27,7 +27,6 @@ def helmholtz_solve(cfg, u_nut, tau, gamma, b, rtol=1e-11, x0=None):
     gamma = gamma0/dt, A = -F^nu of eq. viscous_multiscale with nu_t from
     the enrichment of u_nut), by GMRES on the M^{-1}-scaled form
     gamma x + M^{-1} A x = gamma b.  Returns (x, GMRES iterations)."""
-    require_l0(cfg)
     import scipy.sparse.linalg as sla
     psi = _psi(cfg, tau)
     n = cfg.n_vel
@@ -51,7 +50,6 @@ def helmholtz_solve(cfg, u_nut, tau, gamma, b, rtol=1e-11, x0=None):
 
 def helmholtz_residual(cfg, u_nut, tau, gamma, b, x):
     """gamma M x + A x - gamma M b with the forward mass matrix (no inverse)."""
-    require_l0(cfg)
     psi = _psi(cfg, tau)
     u_nut = np.zeros(cfg.n_vel) if u_nut is None else u_nut
     return gamma * mass_apply(cfg, x, psi) + viscous_multiscale(cfg, x, u_nut=u_nut, tau=tau) \

@@ -125,8 +125,51 @@ def test_l0_only_operators_refuse_l1():
     with pytest.raises(RuntimeError):
         O.velocity_divergence(cfg, u, tau)
     with pytest.raises(RuntimeError):
-        O.viscous_multiscale(cfg, u, tau=tau)
+        O.divdiv_tau(cfg, u, 0.1, tau)
     with pytest.raises(NotImplementedError):
-        OP.mass_apply(cfg, u, np.ones((cfg.n_enriched, 1)))
+        OP.project(cfg, u, np.ones((cfg.n_enriched, 1)), np.ones((cfg.n_enriched, 1)))
     with pytest.raises(NotImplementedError):
         OS.vorticity_rhs(cfg, u, tau)
+
+
+def _rep8(cfg0, v):
+    n = cfg0.ncell * 3 * (cfg0.k_u + 1) ** 3
+    return np.concatenate([v[:n], np.repeat(v[n:].reshape(-1, 3)[:, :, None], 8, axis=2).ravel()])
+
+
+def test_l1_mass_partition_of_unity_and_inverse():
+    """The l = 1 mass matrix: eight equal coefficients give the l = 0 product
+    (polynomial rows equal, enrichment rows summing to the l = 0 row), and
+    inverse_mass inverts mass_apply."""
+    wl = CASES_POU["k3_lower_only"]
+    cfg0 = wl.mesh
+    cfg1 = cfg0.with_(enrich_degree=1)
+    inp = draw_inputs(wl)
+    psi = O.psi_volume(cfg0, O.enriched_cells(cfg0), tau=inp["tau"])
+    n = cfg0.ncell * 3 * (cfg0.k_u + 1) ** 3
+    y0 = OP.mass_apply(cfg0, inp["u"], psi)
+    y1 = OP.mass_apply(cfg1, _rep8(cfg0, inp["u"]), psi)
+    scale = np.abs(y0).max()
+    assert np.abs(y1[:n] - y0[:n]).max() <= 1e-14 * scale
+    assert np.abs(y1[n:].reshape(-1, 3, 8).sum(axis=2) - y0[n:].reshape(-1, 3)).max() <= 1e-14 * scale
+    x = np.random.default_rng(90).uniform(-1, 1, cfg1.n_vel)
+    back = OP.inverse_mass(cfg1, OP.mass_apply(cfg1, x, psi), psi)
+    x_, conds = OP.inverse_mass(cfg1, OP.mass_apply(cfg1, x, psi), psi, return_cond=True)
+    # forward error within the blocks' conditioning
+    err = np.abs(back - x).max()
+    assert err <= 1e3 * np.finfo(float).eps * conds.max() * np.abs(x).max()
+
+
+def test_l1_helmholtz_oracle_solves_its_equation():
+    wl = Workload("l1h", MeshConfig(nx=2, ny=3, nz=2, gamma=1.0, k_u=2, nq_u=4, nq_wn=8, k_p=1, nq_p=2,
+                                    nu=1.0 / 400, enrich_degree=1), 91, 0.5, 1.5)
+    cfg = wl.mesh
+    inp = draw_inputs(wl)
+    rng = np.random.default_rng(92)
+    b = rng.uniform(-1, 1, cfg.n_vel)
+    u_nut = rng.uniform(-1, 1, cfg.n_vel)
+    x, its = OS.helmholtz_solve(cfg, u_nut, inp["tau"], 30.0, b)
+    r = OS.helmholtz_residual(cfg, u_nut, inp["tau"], 30.0, b, x)
+    psi = O.psi_volume(cfg, O.enriched_cells(cfg), tau=inp["tau"])
+    assert np.abs(r).max() <= 1e-9 * 30.0 * np.abs(OP.mass_apply(cfg, b, psi)).max()
+    assert its > 0

@@ -19,6 +19,11 @@ viscous_multiscale) and of its eddy viscosity (Sec. 2.2, eqs. mix, lmix, ydes).
   semi-definite for any nu_t field, here at nu_t/nu up to about 60.
 - The eddy viscosity at a point against its closed form.  With l = 0,
   grad u~ = ut (x) grad psi, so |eps(u~)| = sqrt(|ut|^2 |grad psi|^2 + (ut . grad psi)^2).
+- Degree-1 enrichment weights (Sec. 3.1 eq. enrichment, l = 1): the energy
+  identity with u~ = psi sum_B N_B ut_B evaluated here from the trilinear
+  vertex functions, the reduction to l = 0 when the eight coefficients of
+  every component are equal (the vertex functions sum to one), and the eddy
+  viscosity from grad u~ = sum_B ut_B (x) (N_B grad psi + psi grad N_B).
 """
 import math
 
@@ -58,6 +63,28 @@ class _Basis:
         return val, g
 
 
+def _vertex(xi, h):
+    """Trilinear vertex functions N_B (B = bx + 2 (by + 2 bz)) and their
+    physical gradients on a box cell of sizes h."""
+    N = np.zeros(8)
+    dN = np.zeros((8, 3))
+    for B in range(8):
+        bits = (B & 1, (B >> 1) & 1, B >> 2)
+        f = [xi[d] if bits[d] else 1.0 - xi[d] for d in range(3)]
+        df = [(1.0 if bits[d] else -1.0) / h[d] for d in range(3)]
+        N[B] = f[0] * f[1] * f[2]
+        dN[B] = [df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]]
+    return N, dN
+
+
+def _enr_grad(coef, ps, xi, h):
+    """u~ and grad u~ [c][d] from coefficients coef (3, nle) and psi, grad psi."""
+    if coef.shape[1] == 1:
+        return ps[0] * coef[:, 0], np.outer(coef[:, 0], ps[1:])
+    N, dN = _vertex(xi, h)
+    return ps[0] * coef @ N, coef @ (N[:, None] * ps[None, 1:] + ps[0] * dN)
+
+
 def _gauss(n):
     x, w = np.polynomial.legendre.leggauss(n)
     return 0.5 * (x + 1), 0.5 * w
@@ -85,11 +112,11 @@ class _Field:
         ut, gt, nut = np.zeros(3), np.zeros((3, 3)), 0.0
         k = self.enr.get(e)
         if k is not None:
-            off = self.cfg.ncell * 3 * self.n3 + 3 * k
-            coef = self.u[off:off + 3]
+            nle = (getattr(self.cfg, "enrich_degree", 0) + 1) ** 3
+            off = self.cfg.ncell * 3 * self.n3 + 3 * nle * k
+            coef = self.u[off:off + 3 * nle].reshape(3, nle)
             ps = O.psi_point(self.cfg, self.tau, e, xi)
-            ut = ps[0] * coef
-            gt = np.outer(coef, ps[1:])
+            ut, gt = _enr_grad(coef, ps, xi, self.h(e))
             nut = O.eddy_viscosity_point(self.cfg, self.u_nut, e, xi, tau=self.tau)[0]
         return ub, gb, ut, gt, nut
 
@@ -174,6 +201,8 @@ MS_CASES = {
     "k2_both": (MeshConfig(nx=2, ny=3, nz=2, gamma=1.0, k_u=2, nq_u=4, nq_wn=8, nu=1.0 / 400), 31),
     # one enriched wall, k = 3, a wall-normal rule of 6 points
     "k3_lower": (MeshConfig(nx=2, ny=3, nz=2, gamma=0.6, k_u=3, nq_u=5, nq_wn=6, nu=1.0 / 300, enrich_upper=0), 32),
+    # degree-1 enrichment weights, both walls
+    "k2_both_l1": (MeshConfig(nx=2, ny=3, nz=2, gamma=1.0, k_u=2, nq_u=4, nq_wn=8, nu=1.0 / 400, enrich_degree=1), 39),
 }
 
 
@@ -313,3 +342,46 @@ def test_harmonic_weights_on_inner_enriched_faces():
     assert np.abs(got - exp).max() <= 1e-12 * np.abs(exp).max(), (got, exp)
     # the weights matter here: with equal weights the result would differ
     assert abs(u_nut[off] - u_nut[off + 3]) > 1
+
+
+@pytest.mark.parametrize("name", ["k2_both", "k3_lower"])
+def test_l1_equal_weights_reduce_to_l0(name):
+    cfg0, seed = MS_CASES[name]
+    cfg1 = cfg0.with_(enrich_degree=1)
+    inp = draw_inputs(Workload("ms", cfg0, seed, 0.5, 1.5))
+    n = cfg0.ncell * 3 * (cfg0.k_u + 1) ** 3
+    un0 = np.random.default_rng(seed + 200).uniform(-1, 1, cfg0.n_vel)
+
+    def rep8(v):
+        return np.concatenate([v[:n], np.repeat(v[n:].reshape(-1, 3)[:, :, None], 8, axis=2).ravel()])
+
+    r0 = O.viscous_multiscale(cfg0, inp["u"], u_nut=un0, tau=inp["tau"])
+    r1 = O.viscous_multiscale(cfg1, rep8(inp["u"]), u_nut=rep8(un0), tau=inp["tau"])
+    scale = np.abs(r0).max()
+    assert np.abs(r1[:n] - r0[:n]).max() <= 1e-13 * scale
+    assert np.abs(r1[n:].reshape(-1, 3, 8).sum(axis=2) - r0[n:].reshape(-1, 3)).max() <= 1e-13 * scale
+
+
+def test_l1_eddy_viscosity_closed_form():
+    cfg, seed = MS_CASES["k2_both_l1"]
+    inp = draw_inputs(Workload("ms", cfg, seed, 0.5, 1.5))
+    u_nut = np.random.default_rng(40).uniform(-1, 1, cfg.n_vel)
+    eta = O.vertex_eta(cfg)
+    n3 = (cfg.k_u + 1) ** 3
+    enr = O.enriched_cells(cfg)
+    for kk in (0, len(enr) - 1):
+        e = int(enr[kk])
+        ey = (e // cfg.nx) % cfg.ny
+        h = np.array([cfg.Lx / cfg.nx, eta[ey + 1] - eta[ey], cfg.Lz / cfg.nz])
+        coef = u_nut[cfg.ncell * 3 * n3 + 24 * kk: cfg.ncell * 3 * n3 + 24 * kk + 24].reshape(3, 8)
+        for xi in ((0.2, 0.1, 0.7), (0.9, 0.6, 0.3), (0.4, 0.0, 0.8)):
+            got = O.eddy_viscosity_point(cfg, u_nut, e, xi, tau=inp["tau"])
+            ps = O.psi_point(cfg, inp["tau"], e, xi)
+            _, gt = _enr_grad(coef, ps, xi, h)
+            eps = math.sqrt(2.0 * np.sum(_sym(gt) ** 2))
+            assert abs(got[3] - eps) <= 1e-13 * eps
+            ch = O.C_DES * h[1] / (cfg.k_u + 1)
+            y = got[1]
+            ydes = 0.0 if y == 0 else (y ** -O.BETA + ch ** -O.BETA) ** (-1 / O.BETA)
+            lmix = cfg.kappa * ydes * (1 - math.exp(-got[2] / cfg.A_plus))
+            assert abs(got[0] - lmix ** 2 * eps) <= 1e-13 * max(lmix ** 2 * eps, 1e-300)
