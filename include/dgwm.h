@@ -95,9 +95,12 @@ typedef struct {
                           /*      dg_update_wall_shear; 0: the enrichment is always on      */
   int32_t enrich_degree;  /* tensor degree l of the enrichment weights (Sec. 3.1, eq.       */
                           /*   enrichment): 0 or 1.  l = 1 is built for flat walls and, of  */
-                          /*   the velocity operators, for dg_apply_velocity_residual and   */
-                          /*   dg_apply_convective; every other entry point that reads or   */
-                          /*   writes a velocity vector returns DG_ERR_UNSUPPORTED for it   */
+                          /*   the velocity operators, for dg_apply_velocity_residual,      */
+                          /*   dg_apply_convective, dg_eddy_viscosity,                      */
+                          /*   dg_apply_viscous_multiscale, dg_apply_inverse_mass and       */
+                          /*   dg_solve_helmholtz; every other entry point that reads or    */
+                          /*   writes a velocity vector (the batched residual included)     */
+                          /*   returns DG_ERR_UNSUPPORTED for it                            */
 } dg_mesh_params;
 
 /* Wall laws for psi = U(y+) (paper Sec. 3.2): Spalding's implicit law with
@@ -206,8 +209,9 @@ void dg_destroy_mesh(dg_mesh* mesh);
  *                    - theta nu eps(phi) : ((u- - u+) (x) n) )_F
  * with the local Lax-Friedrichs Lambda = max(2|u-.n|, 2|u+.n|), mirror data
  * u+ = -u-, grad u+ = grad u- and tau_F x wall_ip_mult on no-slip walls,
- * u = u_bar + psi u~ in enriched cells (test functions N_B e_c and psi e_c),
- * quadrature nq_u^3 (nq_u x nq_wn x nq_u in enriched cells).  M du/dt = -r.
+ * u = u_bar + psi sum_B N^l_B u~_B in enriched cells (test functions N_B e_c
+ * and psi N^l_B e_c; l = 0: psi e_c), quadrature nq_u^3 (nq_u x nq_wn x nq_u
+ * in enriched cells).  M du/dt = -r.
  *   prec: DG_F64 -> u, r are double*; DG_F32 -> float* (psi tables stay FP64).
  *   u, r: device vectors of dg_num_dofs(mesh, 0) entries; u != r. */
 int dg_apply_velocity_residual(const dg_mesh* mesh, dg_prec prec, const void* u, void* r, void* stream);
@@ -251,8 +255,10 @@ int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, 
 /* Inverse of the velocity mass matrix, x = M^{-1} r, so that the
  * semi-discrete momentum balance M du/dt = -R(u) of the residual above (paper
  * Sec. 4.1-4.2) advances explicitly as du/dt = -M^{-1} R(u).  Per cell and
- * component M_ij = (phi_i, phi_j)_e over the cell's local basis (N_B, plus psi
- * in an enriched cell whose enrichment is on) with the cell's own quadrature
+ * component M_ij = (phi_i, phi_j)_e over the cell's local basis (N_B, plus
+ * the enrichment functions psi N^l_B in an enriched cell whose enrichment is
+ * on; l = 1: a Schur complement on the 8 enrichment rows, the Gram matrix of
+ * psi N_B - P(psi N_B)) with the cell's own quadrature
  * rule (nq_u^3; nq_u x nq_wn x nq_u in enriched cells); the enrichment
  * unknowns of a switched-off cell are set to 0.  Block-diagonal (cell-local):
  * regular cells by the tensor product of inverse 1-D mass matrices, enriched
@@ -343,7 +349,8 @@ int64_t dg_eddy_viscosity_points(const dg_mesh* mesh);
 
 /* Eddy viscosity of the RANS scale (paper Sec. 2.2) at every quadrature point
  * of the enriched cells, from the enrichment coefficients of u (u~ = psi ut,
- * l = 0, so grad u~ = ut (x) grad psi):
+ * l = 0, so grad u~ = ut (x) grad psi; l = 1: grad u~ = sum_B ut_B (x)
+ * (N_B grad psi + psi grad N_B)):
  *   nu_t = l_mix^2 |eps(u~)|,  |eps| = sqrt(2 eps : eps)             (eq. mix)
  *   l_mix = kappa y_DES (1 - exp(-y+/A+))                            (eq. lmix)
  *   y_DES = (y^-beta + (c_des h)^-beta)^(-1/beta), 0 at the wall     (eq. ydes)
@@ -359,7 +366,7 @@ int dg_eddy_viscosity(const dg_mesh* mesh, const double* u, double c_des, double
 
 /* Viscous term of the multiscale method (paper Sec. 4.2, eq.
  * viscous_multiscale): out(v) = -F^nu_e(v_bar, v~, u_bar, u~) for every test
- * function v (v_bar = N_B e_c; v~ = psi e_c in enriched cells), with
+ * function v (v_bar = N_B e_c; v~ = psi N^l_B e_c in enriched cells), with
  * F^a(w) = 2 a eps(w), the four row blocks and face-class masks of the
  * equation (adjoint sign -1):
  *   volume:    (eps(v_bar), F^nu(u_bar) + F^nuhat(u~)) + (eps(v~), F^{nu+nu_t}(u~)),

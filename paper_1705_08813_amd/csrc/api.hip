@@ -165,7 +165,10 @@ WsLayout layout(const dg_mesh& m) {
   L.act = o; o = up256(o + sizeof(int32_t) * (size_t)m.nenr);
   L.act_prev = o; o = up256(o + sizeof(int32_t) * (size_t)m.nenr);
   L.minv = o; o = up256(o + sizeof(double) * 2 * m.np_u * m.np_u);
-  L.apoly = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (2 * m.np_u * m.np_u * m.np_u + 2));
+  {
+    const size_t np3 = (size_t)m.np_u * m.np_u * m.np_u;  // l = 1: 8 coefficient vectors and the 8 x 8 inverse Gram matrix
+    L.apoly = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (m.nle == 1 ? 2 * np3 + 2 : 8 * np3 + 64));
+  }
   L.coup = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (9 * m.np_u * m.np_u * m.np_u + 6));
   L.spec = o; o = up256(o + sizeof(double) * spectral_table_doubles(m));
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
@@ -429,7 +432,6 @@ int dg_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, vo
 int dg_apply_inverse_mass(const dg_mesh* m, const double* r, double* x, void* stream) {
   if (!m || !r || !x) return set_error(DG_ERR_ARG, "mesh/r/x is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "inverse mass: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!aligned256(r) || !aligned256(x)) return set_error(DG_ERR_ARG, "r and x must be 256-byte aligned");
   return launch_inverse_mass(m, r, x, static_cast<hipStream_t>(stream));
 }
@@ -492,7 +494,6 @@ int64_t dg_eddy_viscosity_points(const dg_mesh* m) {
 int dg_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double beta, double* nut, void* stream) {
   if (!m || !u || !nut) return set_error(DG_ERR_ARG, "mesh/u/nut is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "eddy viscosity: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!(c_des > 0) || !std::isfinite(c_des) || !(beta > 0) || !std::isfinite(beta))
     return set_error(DG_ERR_ARG, "c_des and beta must be positive and finite");
   if (static_cast<const void*>(u) == static_cast<const void*>(nut)) return set_error(DG_ERR_ARG, "u and nut must not alias");
@@ -503,7 +504,6 @@ int dg_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, double be
 int dg_apply_viscous_multiscale(const dg_mesh* m, const double* nut, const double* u, double* out, void* stream) {
   if (!m || !u || !out || (!nut && m->nenr > 0)) return set_error(DG_ERR_ARG, "mesh/nut/u/out is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "multiscale viscous operator: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (u == out || (nut && (nut == u || nut == out))) return set_error(DG_ERR_ARG, "u, out and nut must not alias");
   if (!aligned256(u) || !aligned256(out) || (nut && !aligned256(nut)))
     return set_error(DG_ERR_ARG, "nut, u and out must be 256-byte aligned");

@@ -306,7 +306,6 @@ int dg_solve_helmholtz(const dg_mesh* m, const double* nut, double gamma0_over_d
   if (!m || !gp || !b || !x || !ws) return set_error(DG_ERR_ARG, "mesh/params/b/x/workspace is NULL");
   if (b == x) return set_error(DG_ERR_ARG, "b and x must not alias");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Helmholtz step is built for flat walls only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (m->nenr > 0 && !nut) return set_error(DG_ERR_ARG, "nut is NULL on a mesh with enriched cells");
   return solve_helmholtz(m, nut, gamma0_over_dt, b, x, gp->rtol, gp->max_iter, gp->restart, ws, ws_bytes, st,
                          static_cast<hipStream_t>(stream));

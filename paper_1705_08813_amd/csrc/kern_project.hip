@@ -106,7 +106,7 @@ struct PsiPoly {
 // coefficients of the L2 projection P psi_c onto the cell's polynomials (K
 // the weighted 1-D mass matrices' tensor product, |det J| cancels), and
 // r[c] = psi_c - P psi_c at the points.  Ends with a barrier.
-template <int NC, int NP, int NQ, int NQY>
+template <int NC, int NP, int NQ, int NQY, int PS = 4>
 __device__ __forceinline__ void psi_poly_part(const double* const* psi, const Tab1d<NP, NQ, NQY>& T,
                                               PsiPoly<NP, NQ, NQY>& L, int tid, double* npsi_out = nullptr) {
   constexpr int NPT = NQ * NQY * NQ;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void psi_poly_part(const double* const* psi, const Ta
     const double w = T.W[qx] * T.Wy[qy] * T.W[qz];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double v = psi[c][q * 4];
+      const double v = psi[c][q * PS];  // (PS: stride of the value table)
       L.r[c * NPT + q] = v;
       L.f[c * NPT + q] = w * v;
     }
@@ -276,6 +276,92 @@ __global__ __launch_bounds__(kPrjThreads) void psi_poly_kernel(const InvMassArgs
   }
 }
 
+// Degree-1 enrichment weights (Sec. 3.1, eq. enrichment, l = 1): the eight
+// enrichment functions phi_B = psi N_B of an enriched cell, N_B its trilinear
+// vertex functions (B = bx + 2 (by + 2 bz)).  With a_B = K^{-1} (N, phi_B)_w
+// and the residual functions r_B = phi_B - P phi_B, the Schur complement of
+// the cell's mass block on its 8 enrichment rows (per component) is |det J| G,
+// G_BB' = (r_B, r_B')_w, formed from the pointwise residuals like the l = 0
+// (r_psi, r_psi).  Cached per enriched cell: a_0 .. a_7, then G^{-1} (zero
+// while the enrichment is switched off).
+__host__ __device__ constexpr int apoly_l1_stride(int np3) { return 8 * np3 + 64; }
+
+template <int NP, int NQ, int NQY>
+__global__ __launch_bounds__(kPrjThreads) void psi_poly_l1_kernel(const InvMassArgs A) {
+  constexpr int NPT = NQ * NQY * NQ, NP3 = NP * NP * NP;
+  __shared__ Tab1d<NP, NQ, NQY> T;
+  __shared__ PsiPoly<NP, NQ, NQY> L;
+  __shared__ double phi[8 * NPT];  // phi_B at the volume points, then r_B
+  __shared__ double G[64];
+  const int tid = threadIdx.x;
+  const int64_t enr = blockIdx.x;
+  load_tab1d<NP, NQ, NQY>(A.tab, A.minv, T, tid);
+  // the Gauss points of both rules follow the tables
+  const double* gx = A.tab + tab_layout(NP, NQ, NQY).size;
+  const double* gy = gx + NQ;
+  const double* ps = A.psi + enr * A.psi_pts * 4;
+  for (int q = tid; q < NPT; q += kPrjThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+    const double v[3][2] = {{1.0 - gx[qx], gx[qx]}, {1.0 - gy[qy], gy[qy]}, {1.0 - gx[qz], gx[qz]}};
+    const double p = ps[q * 4];
+#pragma unroll
+    for (int B = 0; B < 8; ++B) phi[B * NPT + q] = p * (v[0][B & 1] * v[1][(B >> 1) & 1] * v[2][B >> 2]);
+  }
+  __syncthreads();
+  double* out = A.apoly + enr * apoly_l1_stride(NP3);
+  for (int pr = 0; pr < 4; ++pr) {
+    const double* src[2] = {phi + 2 * pr * NPT, phi + (2 * pr + 1) * NPT};
+    psi_poly_part<2, NP, NQ, NQY, 1>(src, T, L, tid);
+    for (int i = tid; i < 2 * NP3; i += kPrjThreads) out[2 * pr * NP3 + i] = L.b[i];
+    for (int q = tid; q < 2 * NPT; q += kPrjThreads) phi[2 * pr * NPT + q] = L.r[q];
+    __syncthreads();
+  }
+  if (tid < 64) {
+    const int B = tid & 7, Bp = tid >> 3;
+    double g = 0.0;
+    for (int q = 0; q < NPT; ++q) {
+      const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+      g += T.W[qx] * T.Wy[qy] * T.W[qz] * phi[B * NPT + q] * phi[Bp * NPT + q];
+    }
+    G[tid] = g;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // G = C C^T (Cholesky), G^{-1} = C^{-T} C^{-1}
+    double c[8][8] = {}, ci[8][8] = {};
+    bool ok = A.act[enr] != 0;
+    for (int j = 0; j < 8 && ok; ++j) {
+      double d = G[j * 8 + j];
+      for (int k = 0; k < j; ++k) d -= c[j][k] * c[j][k];
+      if (!(d > 0.0)) {
+        ok = false;
+        break;
+      }
+      c[j][j] = sqrt(d);
+      for (int i = j + 1; i < 8; ++i) {
+        double v = G[i * 8 + j];
+        for (int k = 0; k < j; ++k) v -= c[i][k] * c[j][k];
+        c[i][j] = v / c[j][j];
+      }
+    }
+    if (ok)
+      for (int j = 0; j < 8; ++j) {  // columns of C^{-1} by forward substitution
+        for (int i = 0; i < 8; ++i) {
+          double v = i == j ? 1.0 : 0.0;
+          for (int k = 0; k < i; ++k) v -= c[i][k] * ci[k][j];
+          ci[i][j] = v / c[i][i];
+        }
+      }
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) {
+        double v = 0.0;
+        if (ok)
+          for (int k = 0; k < 8; ++k) v += ci[k][i] * ci[k][j];
+        out[8 * NP3 + i * 8 + j] = v;
+      }
+  }
+}
+
 constexpr int kImThreads = 64;
 
 // x = M^{-1} r, one wavefront per cell.  ENR = false: regular cells, block
@@ -287,11 +373,13 @@ constexpr int kImThreads = 64;
 // polynomial part of psi:
 //   x~_c = (r~_c - a . r_bar_c) / (|det J| (r_psi, r_psi)),
 //   x_bar_c = |det J|^{-1} K^{-1} r_bar_c - a x~_c.
-template <int NP, bool ENR>
+template <int NP, bool ENR, int LE = 1>
 __global__ __launch_bounds__(kImThreads) void invmass_kernel(const InvMassArgs A, int layer_lo, int nlayers) {
   constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
   __shared__ double u[3 * NP3];
-  __shared__ double sa[ENR ? NP3 : 1];
+  __shared__ double sa[ENR ? LE * NP3 : 1];
+  __shared__ double sxt[3 * LE];  // l = 1: the enrichment unknowns [c][B]
+  __shared__ double sd[3 * LE];   // l = 1: r~ - A r_bar
   const int tid = threadIdx.x;
   const int64_t b = blockIdx.x;
   int64_t e;
@@ -312,7 +400,42 @@ __global__ __launch_bounds__(kImThreads) void invmass_kernel(const InvMassArgs A
   for (int i = 0; i < NP2; ++i) m[i] = A.minv[i];
   const double idet = A.ihx * A.ihy[ey] * A.ihz;
   double xt0 = 0.0, xt1 = 0.0, xt2 = 0.0;
-  if (ENR) {
+  if constexpr (ENR && LE == 8) {
+    // degree-1 weights: x~_c = |det J|^{-1} G^{-1} (r~_c - A r_bar_c), A = [a_B]
+    const double* ap = A.apoly + b * apoly_l1_stride(NP3);
+    for (int i = tid; i < 8 * NP3; i += kImThreads) sa[i] = ap[i];
+    __syncthreads();
+    double d[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) d[i] = 0.0;
+    for (int i = tid; i < NP3; i += kImThreads) {
+#pragma unroll
+      for (int B = 0; B < 8; ++B) {
+        const double ab = sa[B * NP3 + i];
+        d[B] += ab * u[i];
+        d[8 + B] += ab * u[NP3 + i];
+        d[16 + B] += ab * u[2 * NP3 + i];
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int i = 0; i < 24; ++i) d[i] += __shfl_xor(d[i], off, 64);
+    const int64_t eo = A.ncell * 3 * NP3 + b * 24;
+    if (tid == 0)
+#pragma unroll
+      for (int i = 0; i < 24; ++i) sd[i] = A.r[eo + i] - d[i];  // r~_c - A r_bar_c
+    __syncthreads();
+    if (tid < 24) {
+      const int c = tid >> 3, B = tid & 7;
+      double x = 0.0;
+#pragma unroll
+      for (int Bp = 0; Bp < 8; ++Bp) x += ap[8 * NP3 + B * 8 + Bp] * sd[c * 8 + Bp];
+      sxt[tid] = x * idet;
+    }
+    __syncthreads();  // every lane has read u and r~ before anything is overwritten
+    if (tid < 24) A.x[eo + tid] = sxt[tid];
+  } else if (ENR) {
     const double* ap = A.apoly + b * apoly_stride(NP3);
     for (int i = tid; i < NP3; i += kImThreads) sa[i] = ap[i];
     __syncthreads();
@@ -397,7 +520,11 @@ __global__ __launch_bounds__(kImThreads) void invmass_kernel(const InvMassArgs A
 #pragma unroll
       for (int l = 0; l < NP; ++l) s += m[o * NP + l] * x[l];
       s *= idet;
-      if (ENR) s -= sa[b0 + o * NP2] * xc;
+      if constexpr (ENR && LE == 1) s -= sa[b0 + o * NP2] * xc;
+      if constexpr (ENR && LE == 8) {
+#pragma unroll
+        for (int B = 0; B < 8; ++B) s -= sa[B * NP3 + b0 + o * NP2] * sxt[c * 8 + B];
+      }
       xe[c * NP3 + b0 + o * NP2] = s;
     }
   }
@@ -770,7 +897,10 @@ int ensure_psi_poly(const dg_mesh* m, const InvMassArgs& A, hipStream_t s) {
     bool launched = false;
 #define X(p, q, w)                                                                                        \
     if (!launched && m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                 \
-      hipLaunchKernelGGL((psi_poly_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
+      if (m->nle == 8)                                                                                    \
+        hipLaunchKernelGGL((psi_poly_l1_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
+      else                                                                                                \
+        hipLaunchKernelGGL((psi_poly_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
       const int rc = check_hip(hipGetLastError(), "psi polynomial part kernel launch");                   \
       if (rc) return rc;                                                                                  \
       launched = true;                                                                                    \
@@ -801,7 +931,9 @@ int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_
       const int rc = check_hip(hipGetLastError(), "inverse mass kernel launch");                             \
       if (rc) return rc;                                                                                     \
     }                                                                                                        \
-    if (m->nenr > 0)                                                                                         \
+    if (m->nenr > 0 && m->nle == 8)                                                                          \
+      hipLaunchKernelGGL((invmass_kernel<p, true, 8>), dim3((unsigned)m->nenr), dim3(kImThreads), 0, s, A, 0, 0); \
+    else if (m->nenr > 0)                                                                                    \
       hipLaunchKernelGGL((invmass_kernel<p, true>), dim3((unsigned)m->nenr), dim3(kImThreads), 0, s, A, 0, 0); \
     return check_hip(hipGetLastError(), "inverse mass kernel launch");                                       \
   }

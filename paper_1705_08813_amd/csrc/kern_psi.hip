@@ -270,11 +270,14 @@ __global__ void psi_kernel(const PsiArgs A) {
 // exp(-y+/A+)) (eq. lmix), y_DES = y C h / (y^beta + (C h)^beta)^(1/beta), the
 // smooth minimum of eq. ydes written so that it is 0 at the wall, h = dy_e /
 // (k+1).  With l = 0, grad u~ = ut (x) grad psi (ut the cell's enrichment
-// coefficients), |eps| = sqrt(2 eps : eps).  Zero in switched-off cells.
+// coefficients); with l = 1, grad u~ = sum_B ut_B (x) (N_B grad psi + psi
+// grad N_B) over the trilinear vertex functions N_B of the cell (Sec. 3.1,
+// eq. enrichment).  |eps| = sqrt(2 eps : eps).  Zero in switched-off cells.
 struct EddyArgs {
-  const double* ut;  // enrichment block of the velocity, [enr][c]
+  const double* ut;  // enrichment block of the velocity, [enr][c][B]
   double c_des, beta, inv_np;
   double* nut;
+  int nle;           // enrichment functions per component: 1 (l = 0) or 8 (l = 1)
 };
 
 template <int NQ, int NQY>
@@ -298,15 +301,41 @@ __global__ void eddy_kernel(const PsiArgs A, const EddyArgs X) {
   const double ydes = yh * ch / pow(pow(yh, X.beta) + pow(ch, X.beta), 1.0 / X.beta);
   const double lmix = A.kappa * ydes * (1.0 - exp(-yp / A.A_plus));
   const double* g = A.psi + gid * 4 + 1;
-  const double* ut = X.ut + enr * 3;
   double e2 = 0.0;
+  if (X.nle == 1) {
+    const double* ut = X.ut + enr * 3;
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const double eij = 0.5 * (ut[i] * g[j] + ut[j] * g[i]);
-      e2 += eij * eij;
+      for (int j = 0; j < 3; ++j) {
+        const double eij = 0.5 * (ut[i] * g[j] + ut[j] * g[i]);
+        e2 += eij * eij;
+      }
+  } else {
+    const double* ut = X.ut + enr * 24;
+    const double ps = A.psi[gid * 4];
+    const double ih[3] = {1.0 / A.hx, 1.0 / (A.eta[c.ey + 1] - A.eta[c.ey]), 1.0 / A.hz};
+    const double v[3][2] = {{1.0 - p.xix, p.xix}, {1.0 - p.xiy, p.xiy}, {1.0 - p.xiz, p.xiz}};
+    double gt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int B = 0; B < 8; ++B) {
+      const int bx = B & 1, by = (B >> 1) & 1, bz = B >> 2;
+      const double n = v[0][bx] * v[1][by] * v[2][bz];
+      const double dn[3] = {(bx ? ih[0] : -ih[0]) * v[1][by] * v[2][bz], (by ? ih[1] : -ih[1]) * v[0][bx] * v[2][bz],
+                            (bz ? ih[2] : -ih[2]) * v[0][bx] * v[1][by]};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gt[i][j] += ut[i * 8 + B] * (n * g[j] + ps * dn[j]);
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double eij = 0.5 * (gt[i][j] + gt[j][i]);
+        e2 += eij * eij;
+      }
+  }
   X.nut[gid] = lmix * lmix * sqrt(2.0 * e2);
 }
 
@@ -374,6 +403,7 @@ int launch_eddy_viscosity(const dg_mesh* m, const double* u, double c_des, doubl
   X.beta = beta;
   X.inv_np = 1.0 / m->np_u;
   X.nut = nut;
+  X.nle = m->nle;
   const int64_t n = m->nenr * m->psi_pts;
   const unsigned nb = (unsigned)((n + 127) / 128);
 #define X_(a, b)                                                                 \

@@ -243,11 +243,15 @@ __device__ __forceinline__ void load_face_tab(const double* tab, T* s_tab) {
 // "interface" faces, which take the same form with the jump of the full
 // velocity.  Writes the weighted value flux, F_g[c][D], F_g[D][T1] and
 // F_g[D][T2] in the vel_faces_dir layout and adds the face terms of the
-// enrichment test rows to rt.
-template <typename T, bool ENR, int D, int T1, int T2>
+// enrichment test rows to rt.  With degree-1 weights (LE = 8) u~ = psi sum_B
+// N_B ut_B and the test functions are psi N_B e_c; (x1, x2) are the point's
+// tangential reference coordinates, ih the cell's reciprocal sizes and ihn
+// the neighbour's along D.
+template <typename T, bool ENR, int D, int T1, int T2, int LE = 1>
 __device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr)[2][8], int s, int pt, int FP,
                                                   bool wall, int64_t enr_nb, int64_t enr, const T* s_ut,
-                                                  const T* s_nut, T wf, T tau, T* fo, T rt[3]) {
+                                                  const T* s_nut, T wf, T tau, T* fo, T* rt, T x1 = T(0),
+                                                  T x2 = T(0), const T* ih = nullptr, T ihn = T(0)) {
   const T nu = T(M.nu);
   const T sg = s ? T(1) : T(-1);
   const int f = 2 * D + s, fn = 2 * D + (1 - s);
@@ -266,6 +270,7 @@ __device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr
   // enrichment parts: u~ = psi ut, (grad u~ + grad u~^T)_{cD} = ut_c dD psi + ut_D dc psi
   T utm[3] = {0, 0, 0}, stm[3] = {0, 0, 0}, utp[3] = {0, 0, 0}, stp[3] = {0, 0, 0};
   T psim = 0, gpsim[3] = {0, 0, 0}, num = 0, nup = 0;
+  T nB[LE], dB[3][LE];  // degree-1 weights: own vertex functions at the point
   if (ENR) {
     const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + f] + pt) * 4;
     psim = T(ps[0]);
@@ -273,10 +278,24 @@ __device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr
     gpsim[1] = T(ps[2]);
     gpsim[2] = T(ps[3]);
     num = T(M.nut[(size_t)enr * M.psi_pts + M.psi_off[1 + f] + pt]);
+    if constexpr (LE == 1) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      utm[c] = psim * s_ut[c];
-      stm[c] = s_ut[c] * gpsim[D] + s_ut[D] * gpsim[c];
+      for (int c = 0; c < 3; ++c) {
+        utm[c] = psim * s_ut[c];
+        stm[c] = s_ut[c] * gpsim[D] + s_ut[D] * gpsim[c];
+      }
+    } else {
+      T xi[3], L[3], dL[3][3];
+      xi[D] = T(s);
+      xi[T1] = x1;
+      xi[T2] = x2;
+      vertex_fns(xi, ih, nB, dB);
+      vertex_weight(s_ut, nB, dB, L, dL);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        utm[c] = psim * L[c];
+        stm[c] = (L[c] * gpsim[D] + psim * dL[c][D]) + (L[D] * gpsim[c] + psim * dL[D][c]);
+      }
     }
   }
   const bool nb_enr = !wall && enr_nb >= 0;
@@ -292,12 +311,27 @@ __device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr
     const double* ps = M.psi + q * 4;
     const T psip = T(ps[0]);
     const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
-    const T* ut = s_nut + f * 3;
+    const T* ut = s_nut + f * 3 * LE;
     nup = T(M.nut[q]);
+    if constexpr (LE == 1) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      utp[c] = psip * ut[c];
-      stp[c] = ut[c] * gpp[D] + ut[D] * gpp[c];
+      for (int c = 0; c < 3; ++c) {
+        utp[c] = psip * ut[c];
+        stp[c] = ut[c] * gpp[D] + ut[D] * gpp[c];
+      }
+    } else {
+      T xin[3], ihv[3] = {ih[0], ih[1], ih[2]}, nn[8], dn[3][8], L[3], dL[3][3];
+      xin[D] = T(1 - s);
+      xin[T1] = x1;
+      xin[T2] = x2;
+      ihv[D] = ihn;
+      vertex_fns(xin, ihv, nn, dn);
+      vertex_weight(ut, nn, dn, L, dL);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        utp[c] = psip * L[c];
+        stp[c] = (L[c] * gpp[D] + psip * dL[c][D]) + (L[D] * gpp[c] + psip * dL[D][c]);
+      }
     }
   }
   const bool inner = ENR && (wall || nb_enr);
@@ -322,7 +356,7 @@ __device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr
   }
   fo[6 * FP] = wf * hn * J[T1];
   fo[7 * FP] = wf * hn * J[T2];
-  if (ENR) {
+  if constexpr (ENR && LE == 1) {
     const T gn = sg * gpsim[D];
     const T jg = ju[0] * gpsim[0] + ju[1] * gpsim[1] + ju[2] * gpsim[2];
 #pragma unroll
@@ -330,6 +364,24 @@ __device__ __forceinline__ void vel_ms_face_point(const MeshDev& M, const T (&tr
       const T val = inner ? psim * (-Et[c] + tau * nu * ju[c]) + wm * (nu + num) * (ju[c] * gn + (c == D ? jg * sg : T(0)))
                           : psim * (-Eb[c] + tau * nu * ju[c]);
       rt[c] += wf * val;
+    }
+  }
+  if constexpr (ENR && LE == 8) {
+    // test functions phi e_c, phi = psi N_B, grad phi = N_B grad psi + psi grad N_B
+#pragma unroll
+    for (int B = 0; B < 8; ++B) {
+      const T phi = psim * nB[B];
+      T gp[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gp[d] = nB[B] * gpsim[d] + psim * dB[d][B];
+      const T gn = sg * gp[D];
+      const T jg = ju[0] * gp[0] + ju[1] * gp[1] + ju[2] * gp[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T val = inner ? phi * (-Et[c] + tau * nu * ju[c]) + wm * (nu + num) * (ju[c] * gn + (c == D ? jg * sg : T(0)))
+                            : phi * (-Eb[c] + tau * nu * ju[c]);
+        rt[c * 8 + B] += wf * val;
+      }
     }
   }
 }
@@ -350,7 +402,7 @@ template <typename T, int NP, int NQ, int NQY, bool ENR, int D, bool MS = false,
 __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, const T* s_nl, const T* s_nut, T* s_r,
                                               T* s_face, const T* s_ut, int ex, int ey, int ez, int64_t enr, T hx,
                                               T hy, T hz, T ihx, T ihy, T ihz, T* rt) {
-  static_assert(LE == 1 || (LE == 8 && !MS), "degree-1 weights are built for the velocity residual");
+  static_assert(LE == 1 || LE == 8, "enrichment weights of degree 0 or 1");
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr int T1 = D == 0 ? 1 : 0;
   constexpr int T2 = D == 2 ? 1 : 2;
@@ -509,9 +561,10 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
       for (int f = 0; f < 8; ++f) tr[1][f] = TR[((s * 2 + 1) * 8 + f) * FP + pt];
     }
     if constexpr (MS) {
-      vel_ms_face_point<T, ENR, D, T1, T2>(M, tr, s, pt, FP, wall, enr_nb, enr, s_ut, s_nut,
-                                           T(tb1.w[q1]) * T(tb2.w[q2]) * ht1 * ht2, s ? tau1 : tau0, FL + s * 8 * FP + pt,
-                                           rt);
+      vel_ms_face_point<T, ENR, D, T1, T2, LE>(M, tr, s, pt, FP, wall, enr_nb, enr, s_ut, s_nut,
+                                               T(tb1.w[q1]) * T(tb2.w[q2]) * ht1 * ht2, s ? tau1 : tau0,
+                                               FL + s * 8 * FP + pt, rt, T(tb1.g[q1]), T(tb2.g[q2]), ihown,
+                                               s ? ihn1 : ihn0);
       continue;
     }
     T psim = 0, gpsim[3] = {0, 0, 0};
@@ -1498,7 +1551,7 @@ __device__ __forceinline__ void vel_cell_affine(const MeshDev& M, const T* __res
 template <typename T, int NP, int NQ, int NQY, bool ENR, bool CURVED, bool MS = false, int LE = 1>
 __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __restrict__ u, T* __restrict__ r, int b,
                                                  int layer_lo, int nlayers) {
-  static_assert(LE == 1 || (LE == 8 && !CURVED && !MS), "degree-1 weights: flat cells, velocity residual");
+  static_assert(LE == 1 || (LE == 8 && !CURVED), "degree-1 weights: flat cells");
   using Sh = VelShape<T, NP, NQ, NQY>;
   constexpr int NP3 = Sh::NP3, NPTS = Sh::NPTS;
   __shared__ T s_u[3 * NP3];
@@ -1616,27 +1669,52 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
       // tests against 2 nu eps(u_bar) + 2 nuhat eps(u~), nuhat the limited
       // viscosity of eq. minvt; enrichment tests against 2 (nu + nu_t) eps(u~)
       T gt[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      T gps[3] = {0, 0, 0}, nt = nu, nhat = nu;
+      T gps[3] = {0, 0, 0}, nt = nu, nhat = nu, psv = 0;
+      T nB[LE], dB[3][LE];
       if (ENR) {
         const double* ps = M.psi + ((size_t)enr * M.psi_pts + pt) * 4;
+        psv = T(ps[0]);
         gps[0] = T(ps[1]);
         gps[1] = T(ps[2]);
         gps[2] = T(ps[3]);
         nt = nu + T(M.nut[(size_t)enr * M.psi_pts + pt]);
         const T lim = T(2) * sqrt(nu * nt);
         nhat = nt < lim ? nt : lim;
+        if constexpr (LE == 1) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+          for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int d = 0; d < 3; ++d) gt[c][d] = s_ut[c] * gps[d];
+            for (int d = 0; d < 3; ++d) gt[c][d] = s_ut[c] * gps[d];
+        } else {
+          const T xi[3] = {T(tbx.g[qx]), T(tby.g[qy]), T(tbx.g[qz])}, ih3[3] = {ix, iy, iz};
+          T L[3], dL[3][3];
+          vertex_fns(xi, ih3, nB, dB);
+          vertex_weight(s_ut, nB, dB, L, dL);
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) gt[c][d] = L[c] * gps[d] + psv * dL[c][d];
+        }
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
+        T sv[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           const T st = gt[c][d] + gt[d][c];
-          if (ENR) rt[c] += wq * nt * st * gps[d];
+          sv[d] = st;
+          if (ENR && LE == 1) rt[c] += wq * nt * st * gps[d];
           s_grad[(c * 3 + d) * NPTS + pt] = wq * (nu * (gg[c][d] + gg[d][c]) + nhat * st);
+        }
+        if constexpr (ENR && LE == 8) {
+          // eps(phi e_c) : F = sum_d d_d phi F[c][d], phi = psi N_B
+#pragma unroll
+          for (int B = 0; B < 8; ++B) {
+            T a = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a += sv[d] * (nB[B] * gps[d] + psv * dB[d][B]);
+            rt[c * 8 + B] += wq * nt * a;
+          }
         }
       }
       continue;
@@ -1821,13 +1899,13 @@ __global__ __launch_bounds__(256, (vel_wg_per_cu<T, NP, NQ, NQY, ENR, CURVED, LE
 
 // Multiscale viscous operator (FP64, flat cells): the general cell path in
 // its viscous-only mode.
-template <int NP, int NQ, int NQY, bool ENR>
-__global__ __launch_bounds__(256, 3) void visc_ms_kernel(const MeshDev M, const double* __restrict__ u,
+template <int NP, int NQ, int NQY, bool ENR, int LE = 1>
+__global__ __launch_bounds__(256, (LE == 8 && ENR) ? 2 : 3) void visc_ms_kernel(const MeshDev M, const double* __restrict__ u,
                                                          double* __restrict__ r, int layer_lo, int nlayers) {
   const int nb = gridDim.x, bid = blockIdx.x;
   const int q8 = nb >> 3, r8 = nb & 7, xcd = bid & 7, m8 = bid >> 3;
   const int blk = xcd * q8 + (xcd < r8 ? xcd : r8) + m8;
-  vel_cell_general<double, NP, NQ, NQY, ENR, false, true>(M, u, r, blk, layer_lo, nlayers);
+  vel_cell_general<double, NP, NQ, NQY, ENR, false, true, LE>(M, u, r, blk, layer_lo, nlayers);
 }
 
 // One mesh of a batched launch.
@@ -2006,10 +2084,31 @@ static int launch_visc_ms_t(const dg_mesh* m, MeshDev M, const double* u, double
   return check_hip(hipGetLastError(), "multiscale viscous kernel launch");
 }
 
+// Degree-1 enrichment weights: the regular cells read the 24 coefficients of
+// an enriched neighbour.
+template <int NP, int NQ, int NQW>
+static int launch_visc_ms_l1_t(const dg_mesh* m, MeshDev M, const double* u, double* r, hipStream_t s) {
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  if (nl > 0)
+    hipLaunchKernelGGL((visc_ms_kernel<NP, NQ, NQ, false, 8>), dim3((unsigned)((int64_t)m->P.nx * nl * m->P.nz)),
+                       dim3(256), 0, s, M, u, r, lo, nl);
+  hipLaunchKernelGGL((visc_ms_kernel<NP, NQ, NQW, true, 8>), dim3((unsigned)m->nenr), dim3(256), 0, s, M, u, r, 0, 0);
+  return check_hip(hipGetLastError(), "multiscale viscous kernel launch");
+}
+
 int launch_viscous_multiscale(const dg_mesh* m, const double* nut, const double* u, double* out, hipStream_t s) {
   MeshDev M = make_meshdev_u(m);
   M.nut = nut;
   const int np = m->np_u, nq = m->P.nq_u, nqw = m->P.nq_wn;
+  if (m->nle != 1 && m->nenr > 0) {
+#define X(a, b, c) \
+  if (np == a && nq == b && nqw == c) return launch_visc_ms_l1_t<a, b, c>(m, M, u, out, s);
+    DG_VEL_L1_COMBOS(X)
+#undef X
+    return set_error(DG_ERR_UNSUPPORTED, "degree-1 enrichment weights: combination not compiled");
+  }
 #define X(a, b, c)                                                        \
   if (np == a && nq == b && (nqw == c || m->nenr == 0)) return launch_visc_ms_t<a, b, c>(m, M, u, out, s);
   DG_VEL_COMBOS(X)

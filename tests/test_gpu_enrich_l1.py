@@ -1,7 +1,8 @@
-"""GPU velocity residual with degree-1 enrichment weights (Sec. 3.1 eq.
+"""GPU operators with degree-1 enrichment weights (Sec. 3.1 eq.
 enrichment, l = 1: psi times the eight trilinear vertex functions, 24
 enrichment unknowns per enriched cell) against the CPU oracle, through the C
-ABI.
+ABI: the velocity residual, and the pieces of the Helmholtz step (eddy
+viscosity, multiscale viscous operator, inverse mass, GMRES solve).
 
 FP64: polynomial and enrichment blocks each at 1e-12 of the oracle's largest
 value, as for l = 0.  FP32: elementwise against the oracle's absolute-value
@@ -15,12 +16,17 @@ import pytest
 import torch
 
 import oracle as O
+from numerics import backward_error
+from oracle import project as OP
+from oracle import step as OS
 from paper_1705_08813_amd import DgError, Mesh
 from paper_1705_08813_amd.inputs import PRESETS, MeshConfig, Workload, draw_inputs
+from test_gpu_multiscale import _nut_oracle
 
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
+EPS = 2.0 ** -52
 
 CASES = {
     "tiny": Workload("l1t", PRESETS["tiny"].mesh.with_(enrich_degree=1), 81, 0.5, 1.5),
@@ -110,7 +116,7 @@ def test_l1_unsupported_entry_points():
     wl = CASES["tiny"]
     mesh = Mesh(wl.mesh, draw_inputs(wl)["tau"])
     u = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
-    for call in (lambda: mesh.apply_inverse_mass(u), lambda: mesh.vorticity(u),
+    for call in (lambda: mesh.project_velocity(u), lambda: mesh.vorticity(u),
                  lambda: mesh.apply_velocity_divergence(u)):
         with pytest.raises(DgError) as ei:
             call()
@@ -120,3 +126,110 @@ def test_l1_unsupported_entry_points():
     assert ei.value.code == -6
     with pytest.raises(DgError):
         Mesh(PRESETS["tiny"].mesh.with_(enrich_degree=2))
+
+
+MS_CASES = {
+    "k2_both": Workload("l1m2", MeshConfig(nx=3, ny=4, nz=2, gamma=1.3, k_u=2, nq_u=4, nq_wn=8, k_p=1, nq_p=2,
+                                           nu=1.0 / 800, enrich_degree=1), 93, 0.5, 1.5),
+    "k3_lower": Workload("l1m3", MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3,
+                                            nu=1.0 / 400, enrich_upper=0, enrich_degree=1), 94, 0.5, 1.5),
+    "k4_both": Workload("l1m4", MeshConfig(nx=3, ny=3, nz=2, gamma=1.2, k_u=4, nq_u=7, nq_wn=8, nu=1.0 / 1000,
+                                           enrich_degree=1), 95, 0.5, 1.5),
+    "k3_switch_off": Workload("l1m5", MeshConfig(nx=3, ny=3, nz=2, gamma=1.0, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3,
+                                                 nu=1.0 / 400, yplus_off=275.0, enrich_degree=1), 96, 0.5, 1.5),
+}
+
+
+@pytest.mark.parametrize("name", list(MS_CASES))
+def test_l1_eddy_viscosity_and_multiscale(name):
+    wl = MS_CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] l=1 eddy viscosity + multiscale viscous case={name}")
+    inp = draw_inputs(wl)
+    u_nut = np.random.default_rng(97).uniform(-1, 1, cfg.n_vel)
+    mesh = Mesh(cfg, inp["tau"])
+    nut = mesh.eddy_viscosity(torch.tensor(u_nut, device="cuda"))
+    ref_nut = _nut_oracle(cfg, u_nut, inp["tau"], O.enriched_cells(cfg))
+    e_nut = _rel(nut.cpu().numpy(), ref_nut.ravel())
+    out = mesh.apply_viscous_multiscale(nut, torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    ref = O.viscous_multiscale(cfg, inp["u"], u_nut=u_nut, tau=inp["tau"])
+    op, oe = _split(cfg, out)
+    rp, re = _split(cfg, ref)
+    _log(f"[gpu]   nu_t rel {e_nut:.1e} (max nu_t/nu {ref_nut.max() / cfg.nu:.1f}); rel poly {_rel(op, rp):.1e} "
+         f"enr {_rel(oe, re):.1e}")
+    assert e_nut <= 1e-12
+    assert _rel(op, rp) <= 1e-12 and _rel(oe, re) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(MS_CASES))
+def test_l1_inverse_mass(name):
+    """Regular cells at 1e-12; each enriched cell (block of 3 (n^3 + 8)
+    unknowns) by its forward error within 64 eps cond(M_cell) and its
+    backward error ||M x - r|| <= 2 n eps (||M|| ||x|| + ||r||) per component
+    with the oracle's block."""
+    wl = MS_CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] l=1 inverse mass case={name}")
+    inp = draw_inputs(wl)
+    cells = O.enriched_cells(cfg)
+    psi = O.psi_volume(cfg, cells, tau=inp["tau"])
+    act = O.enrichment_active(cfg, tau=inp["tau"])
+    psi = psi * act[:, None]
+    r = np.random.default_rng(98).uniform(-1, 1, cfg.n_vel)
+    mesh = Mesh(cfg, inp["tau"])
+    x = mesh.apply_inverse_mass(torch.tensor(r, device="cuda")).cpu().numpy()
+    ref, conds = OP.inverse_mass(cfg, r, psi, return_cond=True)
+    n1 = (cfg.k_u + 1) ** 3
+    off = cfg.ncell * 3 * n1
+    enr = {int(e): k for k, e in enumerate(cells)}
+    worst_f = worst_b = 0.0
+    for e in range(cfg.ncell):
+        idx = np.arange(e * 3 * n1, (e + 1) * 3 * n1)
+        k = enr.get(e)
+        if k is None:
+            assert np.abs(x[idx] - ref[idx]).max() <= 1e-12 * max(np.abs(ref[idx]).max(), 1e-300)
+            continue
+        idx = np.concatenate([idx, off + 24 * k + np.arange(24)])
+        err = np.abs(x[idx] - ref[idx]).max() / max(np.abs(ref[idx]).max(), 1e-300)
+        tol = max(1e-12, 64 * EPS * conds[e])
+        worst_f = max(worst_f, err / tol)
+        assert err <= tol, (e, err, tol)
+        M = OP.mass_block(cfg, e, psi[k])
+        for c in range(3):
+            rows = np.arange((e * 3 + c) * n1, (e * 3 + c + 1) * n1)
+            if M.shape[0] == n1 + 8:
+                rows = np.append(rows, off + 24 * k + 8 * c + np.arange(8))
+            eta = backward_error(M, x[rows], r[rows])
+            worst_b = max(worst_b, eta / EPS)
+            assert eta <= 2 * M.shape[0] * EPS, (e, c, eta / EPS)
+    _log(f"[gpu]   max cond {conds.max():.1e}, worst forward/tol {worst_f:.2f}, worst backward {worst_b:.1f} eps")
+
+
+@pytest.mark.parametrize("name", ["k2_both", "k3_lower"])
+def test_l1_helmholtz_and_iterations_against_l0(name):
+    """The Helmholtz step (Sec. 4.2 eq. helmholtzspat) with l = 1 by the
+    forward residual of the paper's equation with the oracle's operators,
+    and its GMRES iteration count against the same mesh with l = 0 (Sec. 5.1
+    reports about three times as many for l = 1)."""
+    wl = MS_CASES[name]
+    cfg1 = wl.mesh
+    cfg0 = cfg1.with_(enrich_degree=0)
+    inp = draw_inputs(wl)
+    rng = np.random.default_rng(99)
+    gamma = 300.0
+    its = {}
+    for cfg in (cfg0, cfg1):
+        b = rng.uniform(-1, 1, cfg.n_vel)
+        u_nut = rng.uniform(-1, 1, cfg.n_vel)
+        mesh = Mesh(cfg, inp["tau"])
+        nut = mesh.eddy_viscosity(torch.tensor(u_nut, device="cuda"))
+        x, st = mesh.solve_helmholtz(nut, gamma, torch.tensor(b, device="cuda"), rtol=1e-10)
+        res = OS.helmholtz_residual(cfg, u_nut, inp["tau"], gamma, b, x.cpu().numpy())
+        psi = O.psi_volume(cfg, O.enriched_cells(cfg), tau=inp["tau"])
+        scale = gamma * np.abs(OP.mass_apply(cfg, b, psi)).max()
+        its[cfg.enrich_degree] = st.iterations
+        _log(f"[gpu]   l={cfg.enrich_degree}: GMRES its {st.iterations} rel {st.rel_resid:.1e} "
+             f"fwd resid/scale {np.abs(res).max() / scale:.1e}")
+        assert st.rel_resid <= 1e-10
+        assert np.abs(res).max() <= 1e-8 * scale
+    _log(f"[gpu]   iterations l=1 / l=0 = {its[1] / max(its[0], 1):.2f}")
