@@ -672,7 +672,7 @@ int dg_dual_splitting_step(const dg_mesh* mesh, const dg_step_params* sp, const 
 
 const char* dg_last_error(void);
 
-/* Degree / quadrature combinations compiled into this build, as text. */
+/* Degree / quadrature combinations compiled into the library, as text. */
 const char* dg_build_info(void);
 
 #ifdef __cplusplus
