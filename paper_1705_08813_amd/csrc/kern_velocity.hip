@@ -466,17 +466,15 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
 
   // Phase B1: lines along t1 (node i1 -> Gauss q1).  Fields: 0-2 value of
   // u_c, 3-5 normal derivative of u_c, 6 t1-derivative of u_D.
-  // (lines of field 6 come last, so only one wavefront runs both branches)
-  for (int t = tid; t < 2 * 2 * 7 * NP; t += nt) {
-    constexpr int N0 = 2 * 2 * 6 * NP;
-    const bool last = t >= N0;
-    const int tt = last ? t - N0 : t;
-    const int i2 = tt % NP;
-    int r = tt / NP;
-    const int f = last ? 6 : r % 6;
-    if (!last) r /= 6;
-    const int side = r % 2, s = r / 2;
-    if (side == 1 && (s ? wall1 : wall0)) continue;
+  // Thread t takes line i2 = t & 7 of side (t >> 3) & 1, face (t >> 4) & 1,
+  // field t >> 5: two fields per wavefront, so the derivative field 6 has
+  // wavefront 3 to itself and no wavefront runs both branches; the index
+  // decomposition is shifts and masks (NP <= 8).
+  static_assert(NP <= 8 && Q1 <= 8 && Q2 <= 8, "face phases index lines and points in 3 bits");
+  {
+    const int t = tid;
+    const int i2 = t & 7, side = (t >> 3) & 1, s = (t >> 4) & 1, f = t >> 5;
+    if (f < 7 && i2 < NP && !(side == 1 && (s ? wall1 : wall0))) {
     const int c = f < 3 ? f : (f < 6 ? f - 3 : D);
     const int fld = (f >= 3 && f < 6) ? 1 : 0;
     const T* lv = (side == 0 ? lay + ((s * 3 + c) * 2) * NP2 : s_nl + (((2 * D + s) * 3 + c) * 2) * NP2) +
@@ -502,22 +500,18 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
         o[q1 * NP] = acc;
       }
     }
+    }
   }
   __syncthreads();
 
   // Phase C1: lines along t2 (node i2 -> Gauss q2), giving the 8 trace
   // fields of each side; field 7 = d_T2 u_D from the value of u_D.
-  // (lines of field 7 come last, so only one wavefront runs both branches)
-  for (int t = tid; t < 2 * 2 * 8 * Q1; t += nt) {
-    constexpr int N0 = 2 * 2 * 7 * Q1;
-    const bool last = t >= N0;
-    const int tt = last ? t - N0 : t;
-    const int q1 = tt % Q1;
-    int r = tt / Q1;
-    const int fo = last ? 7 : r % 7;
-    if (!last) r /= 7;
-    const int side = r % 2, s = r / 2;
-    if (side == 1 && (s ? wall1 : wall0)) continue;
+  // Thread t takes line q1 = t & 7 of side (t >> 3) & 1, face (t >> 4) & 1,
+  // field t >> 5 (so only wavefront 3, fields 6 and 7, runs both branches).
+  {
+    const int t = tid;
+    const int q1 = t & 7, side = (t >> 3) & 1, s = (t >> 4) & 1, fo = t >> 5;
+    if (q1 < Q1 && !(side == 1 && (s ? wall1 : wall0))) {
     const int fin = fo < 7 ? fo : D;
     const T* a = A1 + (((s * 2 + side) * 7 + fin) * Q1 + q1) * NP;
     T x[NP];
@@ -541,14 +535,17 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
         o[q2 * Q1] = acc;
       }
     }
+    }
   }
   __syncthreads();
 
-  // Phase C2: numerical flux at each face point
+  // Phase C2: numerical flux at each face point (thread t: q1 = t & 7,
+  // q2 = (t >> 3) & 7, face t >> 6; one pass over the first 128 threads)
   const T nu = T(M.nu), theta = T(M.theta);
-  for (int t = tid; t < 2 * FP; t += nt) {
-    const int s = t / FP, pt = t - s * FP;
-    const int q1 = pt % Q1, q2 = pt / Q1;
+  for (int t = tid; t < 2 * 64; t += nt) {
+    const int q1 = t & 7, q2 = (t >> 3) & 7, s = t >> 6;
+    if (q1 >= Q1 || q2 >= Q2) continue;
+    const int pt = q1 + Q1 * q2;
     const T sg = s ? T(1) : T(-1);
     const bool wall = s ? wall1 : wall0;
     const int64_t enr_nb = s ? enrn1 : enrn0;
@@ -687,22 +684,12 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   // Phase D1: lines along t2 transposed (q2 -> i2).  Tests 0-2: value test
   // S2^T fv_c (+ Sd2^T F[D][T2] / ht2 for c = D); 3: t1-derivative test
   // S2^T F[D][T1]; 4-6: normal-derivative test S2^T F[c][D].
-  // (the tests o = D, which add the Sd2 part, come last)
-  for (int t = tid; t < 2 * 7 * Q1; t += nt) {
-    constexpr int N0 = 2 * 6 * Q1;
-    const bool last = t >= N0;
-    const int tt = last ? t - N0 : t;
-    const int q1 = tt % Q1;
-    int r = tt / Q1;
-    int o, s;
-    if (last) {
-      o = D;
-      s = r;
-    } else {
-      const int oi = r % 6;
-      o = oi < D ? oi : oi + 1;
-      s = r / 6;
-    }
+  // (thread t: q1 = t & 7, face (t >> 3) & 1, test slot k = t >> 4; the
+  // tests o = D, which add the Sd2 part, take slot 6, in wavefront 1 only)
+  for (int t = tid; t < 7 * 16; t += nt) {
+    const int q1 = t & 7, s = (t >> 3) & 1, k = t >> 4;
+    if (q1 >= Q1) continue;
+    const int o = k == 6 ? D : (k < D ? k : k + 1);
     const int fin = o < 3 ? o : (o == 3 ? 6 : o - 1);
     const T* a = FL + (s * 8 + fin) * FP + q1;
     T x[Q2];
