@@ -101,6 +101,10 @@ typedef struct {
                           /*   dg_solve_helmholtz; every other entry point that reads or    */
                           /*   writes a velocity vector (the batched residual included)     */
                           /*   returns DG_ERR_UNSUPPORTED for it                            */
+  int32_t omit_step_tables; /* 1: the mesh workspace leaves out the projection-step tables  */
+                          /*   (per-layer spectral factors, enriched-cell couplings), so    */
+                          /*   dg_projection_step and dg_dual_splitting_step return         */
+                          /*   DG_ERR_UNSUPPORTED on the mesh; 0 (default): reserved         */
 } dg_mesh_params;
 
 /* Wall laws for psi = U(y+) (paper Sec. 3.2): Spalding's implicit law with

@@ -35,7 +35,7 @@ class MeshParams(ctypes.Structure):
         ("ip_factor_u", ctypes.c_double), ("ip_factor_p", ctypes.c_double),
         ("wall_ip_mult", ctypes.c_double), ("theta", ctypes.c_double),
         ("psi_kind", ctypes.c_int32), ("A_plus", ctypes.c_double), ("yplus_off", ctypes.c_double),
-        ("enrich_degree", ctypes.c_int32),
+        ("enrich_degree", ctypes.c_int32), ("omit_step_tables", ctypes.c_int32),
     ]
 
 

@@ -101,6 +101,7 @@ int derive(const dg_mesh_params& P, dg_mesh& m) {
   if (!(P.yplus_off >= 0) || !std::isfinite(P.yplus_off))
     return set_error(DG_ERR_ARG, "yplus_off must be >= 0 and finite");
   if (P.enrich_degree != 0 && P.enrich_degree != 1) return set_error(DG_ERR_ARG, "enrich_degree must be 0 or 1");
+  if (P.omit_step_tables != 0 && P.omit_step_tables != 1) return set_error(DG_ERR_ARG, "omit_step_tables must be 0 or 1");
   if (P.enrich_degree == 1 && P.wall_amp != 0.0)
     return set_error(DG_ERR_UNSUPPORTED, "degree-1 enrichment weights are built for flat walls only");
   if (P.wall_amp != 0.0 && P.fully_periodic) return set_error(DG_ERR_ARG, "a curved wall needs walls");
@@ -169,8 +170,10 @@ WsLayout layout(const dg_mesh& m) {
     const size_t np3 = (size_t)m.np_u * m.np_u * m.np_u;  // l = 1: 8 coefficient vectors and the 8 x 8 inverse Gram matrix
     L.apoly = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (m.nle == 1 ? 2 * np3 + 2 : 8 * np3 + 64));
   }
-  L.coup = o; o = up256(o + sizeof(double) * (size_t)m.nenr * (9 * m.np_u * m.np_u * m.np_u + 6));
-  L.spec = o; o = up256(o + sizeof(double) * spectral_table_doubles(m));
+  // projection-step tables (left out on request)
+  const bool st = !m.P.omit_step_tables;
+  L.coup = o; o = up256(o + (st ? sizeof(double) * (size_t)m.nenr * (9 * m.np_u * m.np_u * m.np_u + 6) : 0));
+  L.spec = o; o = up256(o + (st ? sizeof(double) * spectral_table_doubles(m) : 0));
   L.diag = o; o = up256(o + sizeof(double) * m.n_p);
   L.diag32 = o; o = up256(o + sizeof(float) * m.n_p);
   L.geo = o; o = up256(o + sizeof(double) * 10 * (size_t)m.ncell * m.geo_stride);

@@ -945,6 +945,8 @@ int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_
 
 int launch_projection_step(const dg_mesh* m, const double* tau_d, const double* u_hat, const double* g, double scale,
                            double* x, hipStream_t s) {
+  if (m->P.omit_step_tables)
+    return set_error(DG_ERR_UNSUPPORTED, "the mesh was set up without projection-step tables (omit_step_tables)");
   int rc = ensure_spectral_tables(m, s);
   // cells without enrichment: direct solve per layer
   if (!rc) rc = launch_spectral_step(m, tau_d, u_hat, g, scale, x, s);

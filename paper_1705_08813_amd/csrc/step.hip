@@ -109,6 +109,8 @@ int dg_dual_splitting_step(const dg_mesh* m, const dg_step_params* sp, const dou
   const auto t0 = std::chrono::steady_clock::now();
   if (!m || !sp || !u_n || !u_np1 || !p || !ws) return set_error(DG_ERR_ARG, "mesh/params/u_n/u_np1/p/ws is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the dual-splitting step is built for flat walls only");
+  if (m->P.omit_step_tables)
+    return set_error(DG_ERR_UNSUPPORTED, "the mesh was set up without projection-step tables (omit_step_tables)");
   if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (sp->order != 1 && sp->order != 2) return set_error(DG_ERR_ARG, "order must be 1 or 2");
   if (sp->order == 2 && !u_nm1) return set_error(DG_ERR_ARG, "order 2 needs u_nm1");

@@ -52,6 +52,7 @@ class MeshConfig:
     A_plus: float = 26.0
     yplus_off: float = 0.0     # > 0: switch a wall cell's enrichment off while all its points have y+ below this
     enrich_degree: int = 0     # tensor degree l of the enrichment weights (0: 3, 1: 24 DoFs per enriched cell)
+    omit_step_tables: int = 0  # 1: no projection-step tables in the mesh workspace (operators and solves only)
 
     def as_dict(self):
         return asdict(self)

@@ -36,12 +36,18 @@ from . import Mesh, _lib, apply_velocity_residual_batched, batch_workspace, solv
 from .inputs import Request, ServingConfig, draw_inputs, serving_requests
 
 
+def serving_mesh(wl):
+    """The mesh of a request: its operators and solves need no projection-step
+    tables, so the instance does not reserve them."""
+    return wl.mesh.with_(omit_step_tables=1)
+
+
 def footprint_bytes(wl, sp) -> int:
     """Device bytes one instance holds while admitted: mesh tables, solve
     workspace, velocity input and output, pressure right-hand side and
     solution (FP64)."""
     L = _lib.lib()
-    params = _lib.params_from(wl.mesh)
+    params = _lib.params_from(serving_mesh(wl))
     mesh_ws = _lib.check(L.dg_mesh_workspace_bytes(ctypes.byref(params)))
     solve_ws = _lib.check(L.dg_solve_workspace_bytes_for(ctypes.byref(params), ctypes.byref(sp)))
     m = wl.mesh
@@ -161,7 +167,7 @@ class Server:
         inst.stream = self._stream()
         d = draw_inputs(wl)
         with torch.cuda.device(self.device), torch.cuda.stream(inst.stream):
-            inst.mesh = Mesh(wl.mesh, tau_w=d["tau"], device=self.device, stream=inst.stream)
+            inst.mesh = Mesh(serving_mesh(wl), tau_w=d["tau"], device=self.device, stream=inst.stream)
             inst.u = torch.from_numpy(d["u"]).to(self.device)
             inst.b = torch.from_numpy(d["p"]).to(self.device)
             inst.r = torch.empty_like(inst.u)

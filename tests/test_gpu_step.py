@@ -79,3 +79,26 @@ def test_step_repeats_bitwise_and_chains():
         prev, cur = cur, nxt
         _log(f"[gpu]   chained step: poisson its={st.poisson.outer_its} helmholtz its={st.helmholtz.iterations}")
     assert torch.isfinite(cur).all()
+
+
+def test_mesh_without_step_tables():
+    """A mesh set up with omit_step_tables (as served instances are) applies
+    the operators bit for bit like the full mesh and refuses the projection
+    step and the time step."""
+    from paper_1705_08813_amd import DgError
+    wl = CASES["tiny"]
+    cfg = wl.mesh
+    inp = draw_inputs(wl)
+    full, lean = Mesh(cfg, inp["tau"]), Mesh(cfg.with_(omit_step_tables=1), inp["tau"])
+    u = torch.tensor(inp["u"], device="cuda")
+    assert torch.equal(full.apply_velocity_residual(u), lean.apply_velocity_residual(u))
+    assert torch.equal(full.apply_inverse_mass(u), lean.apply_inverse_mass(u))
+    sp = lean.step_params(0.005, order=1)
+    p = torch.zeros(cfg.n_p, dtype=torch.float64, device="cuda")
+    with pytest.raises(DgError) as ei:
+        lean.dual_splitting_step(sp, u, None, p)
+    assert ei.value.code == -6
+    td = torch.zeros(cfg.ncell, dtype=torch.float64, device="cuda")
+    with pytest.raises(DgError) as ei:
+        lean.projection_step(td, u, torch.zeros_like(u), 1e-3)
+    assert ei.value.code == -6

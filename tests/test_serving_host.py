@@ -36,3 +36,19 @@ def test_footprint_counts_every_resident_buffer():
         # at least the four FP64 vectors plus the solver's 9 FP64 + 9 FP32 work vectors
         assert fp >= 8 * (2 * m.n_vel + 2 * m.n_p) + (9 * 8 + 9 * 4) * m.n_p
         assert fp < 1 << 30
+
+
+def test_serving_footprint_leaves_out_the_projection_step_tables():
+    """Served instances only apply operators and solve, so their meshes are
+    set up without the projection-step tables; the mesh workspace then shrinks
+    by at least the enriched cells' coupling cache (9 (k+1)^3 + 6 doubles per
+    enriched cell) and the per-layer spectral factors (2 n^2 + n doubles per
+    distinct cell height, n = 3 (k+1)^3)."""
+    import ctypes
+    L = _lib.lib()
+    for q in serving_requests(ServingConfig(n_requests=8)):
+        m = q.workload.mesh
+        full = _lib.check(L.dg_mesh_workspace_bytes(ctypes.byref(_lib.params_from(m))))
+        lean = _lib.check(L.dg_mesh_workspace_bytes(ctypes.byref(_lib.params_from(m.with_(omit_step_tables=1)))))
+        n = 3 * (m.k_u + 1) ** 3
+        assert full - lean >= 8 * (m.n_enriched * (9 * (m.k_u + 1) ** 3 + 6) + 2 * n * n + n)
