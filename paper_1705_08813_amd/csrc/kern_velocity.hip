@@ -442,6 +442,28 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
   // neighbours' reciprocal sizes along D (degree-1 weights of an enriched neighbour)
   const T ihn0 = D == 1 ? T(M.ihy[nb0.nidx1]) : ihd, ihn1 = D == 1 ? T(M.ihy[nb1.nidx1]) : ihd;
 
+  // psi and grad psi at this thread's point of the flux phase (C2 mapping),
+  // of the own side (enriched cells) and of an enriched neighbour's side,
+  // loaded here so that their latency overlaps the trace phases
+  T pfo[4] = {0, 0, 0, 0}, pfn[4] = {0, 0, 0, 0};
+  if constexpr (!MS) {
+    const int q1 = tid & 7, q2 = (tid >> 3) & 7, s = tid >> 6;
+    if (tid < 2 * 64 && q1 < Q1 && q2 < Q2) {
+      const int pt = q1 + Q1 * q2;
+      if (ENR) {
+        const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + 2 * D + s] + pt) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pfo[j] = T(ps[j]);
+      }
+      const int64_t en = s ? enrn1 : enrn0;
+      if (!(s ? wall1 : wall0) && en >= 0) {
+        const double* ps = M.psi + ((size_t)en * M.psi_pts + M.psi_off[1 + 2 * D + (1 - s)] + pt) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pfn[j] = T(ps[j]);
+      }
+    }
+  }
+
   // Phase A: own node layers of both faces (value, d/dx_D), one line each
   for (int t = tid; t < 3 * NP2; t += nt) {
     const int c = t / NP2, k = t - c * NP2;
@@ -568,11 +590,10 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
     // degree-1 weights: vertex functions at the face point (own cell, xi_D = s)
     T nB[LE], dB[3][LE];
     if (ENR) {
-      const double* ps = M.psi + ((size_t)enr * M.psi_pts + M.psi_off[1 + 2 * D + s] + pt) * 4;
-      psim = T(ps[0]);
-      gpsim[0] = T(ps[1]);
-      gpsim[1] = T(ps[2]);
-      gpsim[2] = T(ps[3]);
+      psim = pfo[0];
+      gpsim[0] = pfo[1];
+      gpsim[1] = pfo[2];
+      gpsim[2] = pfo[3];
       if constexpr (LE == 1) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -602,9 +623,8 @@ __device__ __forceinline__ void vel_faces_dir(const MeshDev& M, const T* s_u, co
 #pragma unroll
       for (int f = 0; f < 8; ++f) tr[1][f] = (f < 3) ? -tr[0][f] : tr[0][f];
     } else if (enr_nb >= 0) {
-      const double* ps = M.psi + ((size_t)enr_nb * M.psi_pts + M.psi_off[1 + 2 * D + (1 - s)] + pt) * 4;
-      const T psip = T(ps[0]);
-      const T gpp[3] = {T(ps[1]), T(ps[2]), T(ps[3])};
+      const T psip = pfn[0];
+      const T gpp[3] = {pfn[1], pfn[2], pfn[3]};
       const T* ut = s_nut + (2 * D + s) * 3 * LE;
       if constexpr (LE == 1) {
 #pragma unroll
@@ -1590,6 +1610,23 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
   if (ENR && tid < 3 * LE) s_ut[tid] = u[M.enr_off + enr * 3 * LE + tid];
   NbLines<T, NP> nbl;
   nb_fetch<T, NP, LE>(M, u, ex, ey, ez, nbl);
+  // psi and grad psi at the thread's volume points (enriched cells), loaded
+  // with the cell so that their latency overlaps the sweeps
+  constexpr int NPASS = (NPTS + nt - 1) / nt;
+  T pfv[NPASS][4];
+  if constexpr (ENR && !MS) {
+#pragma unroll
+    for (int kp = 0; kp < NPASS; ++kp) {
+      const int pt = tid + kp * nt;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pfv[kp][j] = 0;
+      if (pt < NPTS) {
+        const double* ps = M.psi + ((size_t)enr * M.psi_pts + pt) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pfv[kp][j] = T(ps[j]);
+      }
+    }
+  }
   if (CURVED) load_face_tab<T, NP, NQ, NQY, ENR>(tab, s_tab);
   __syncthreads();
 
@@ -1623,7 +1660,10 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
   for (int i = 0; i < 3 * LE; ++i) rt[i] = 0;
   const T nu = T(M.nu);
   const T vol = hx * hy * hz;
-  for (int pt = tid; pt < NPTS; pt += nt) {
+#pragma unroll
+  for (int kp = 0; kp < NPASS; ++kp) {
+    const int pt = tid + kp * nt;
+    if (pt >= NPTS) break;
     const int qx = pt % NQ, qy = (pt / NQ) % NQY, qz = pt / (NQ * NQY);
     T wq, Ji[3][3];
     if (CURVED) {
@@ -1709,11 +1749,10 @@ __device__ __forceinline__ void vel_cell_general(const MeshDev& M, const T* __re
     T gps[3] = {0, 0, 0}, psv = 0;
     T nB[LE], dB[3][LE];  // degree-1 weights: vertex functions at the point
     if (ENR) {
-      const double* ps = M.psi + ((size_t)enr * M.psi_pts + pt) * 4;
-      psv = T(ps[0]);
-      gps[0] = T(ps[1]);
-      gps[1] = T(ps[2]);
-      gps[2] = T(ps[3]);
+      psv = pfv[kp][0];
+      gps[0] = pfv[kp][1];
+      gps[1] = pfv[kp][2];
+      gps[2] = pfv[kp][3];
       if constexpr (LE == 1) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
