@@ -507,6 +507,28 @@ def main():
             hl["its_ratio_l1_over_l0"] = hl["l1"]["gmres_its"] / hl["l0"]["gmres_its"]
         hl["mesh"] = "16x16x16, tanh grading 1.2, k_u = 4, nu = 1/950, tau_w ~ U[0.5, 1.5], random u"
         extras["helmholtz_l1_vs_l0"] = hl
+        # Poisson iterations on the two meshes of the paper's cost comparison (Sec. 5.1: about 9 iterations for
+        # the wall-modeled 12x8x12 mesh with grading 1.6, 22 for the wall-resolved 24^3 mesh with grading 2.25,
+        # k = 4, pressure k - 1): multigrid-preconditioned CG (FP64 and mixed) from zero, random right-hand side
+        print("bench: Poisson iterations, wall-modeled against wall-resolved mesh", file=sys.stderr, flush=True)
+        pit = {}
+        for name, (nx_, ny_, nz_, gam) in (("wall_modeled_12x8x12_g1.6", (12, 8, 12, 1.6)),
+                                            ("wall_resolved_24x24x24_g2.25", (24, 24, 24, 2.25))):
+            cfg_p = MeshConfig(nx=nx_, ny=ny_, nz=nz_, gamma=gam, k_u=4, nq_u=7, nq_wn=8, k_p=3, nq_p=4,
+                               nu=1.0 / 950, enrich_lower=1 if ny_ == 8 else 0, enrich_upper=1 if ny_ == 8 else 0,
+                               omit_step_tables=1)
+            mp_ = Mesh(cfg_p, np.ones(cfg_p.n_tau), device=dev)
+            bp_ = torch.tensor(np.random.default_rng(6).uniform(-1, 1, cfg_p.n_p), device=dev)
+            row = {}
+            for rt_ in (1e-3, 1e-6, 1e-10):
+                for mixed in (False, True):
+                    spp = mp_.solve_params(rtol=rt_, mixed=mixed)
+                    _, stp = mp_.solve_poisson(bp_, sp=spp, workspace=mp_.solve_workspace(spp))
+                    row[f"{'mixed' if mixed else 'f64'}_rtol{rt_:g}"] = stp.outer_its
+            pit[name] = row
+            del mp_, bp_
+        pit["paper_iterations"] = {"wall_modeled_12x8x12_g1.6": 9, "wall_resolved_24x24x24_g2.25": 22}
+        extras["poisson_iterations_stretching"] = pit
     if not args.no_extras:
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)
