@@ -209,11 +209,13 @@ int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau
   const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
   const int nl = hi - lo + 1;
   const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
-  const int nqw = m->nenr > 0 ? m->P.nq_wn : m->P.nq_u;
+  // without enriched cells only the regular kernels run and nq_wn is irrelevant
+  const bool any_w = m->nenr == 0;
+  const int nqw = m->P.nq_wn;
 #define LAUNCH(KER, p, q, w, ENRV, grid, lo_, nl_) \
   hipLaunchKernelGGL((KER<p, q, w, ENRV>), dim3((unsigned)(grid)), dim3(kDdThreads), 0, s, A, lo_, nl_)
 #define X(p, q, w)                                                                              \
-  if (m->np_u == p && m->P.nq_u == q && nqw == w) {                                             \
+  if (m->np_u == p && m->P.nq_u == q && (any_w || nqw == w)) {                                  \
     if (nreg > 0) {                                                                             \
       if (tau) LAUNCH(divdiv_tau_kernel, p, q, q, false, nreg, lo, nl);                         \
       else LAUNCH(divdiv_apply_kernel, p, q, q, false, nreg, lo, nl);                           \

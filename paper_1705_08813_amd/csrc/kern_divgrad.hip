@@ -409,11 +409,13 @@ int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* 
   const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
   const int nl = hi - lo + 1;
   const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
-  const int nqw = m->nenr > 0 ? m->P.nq_wn : m->P.nq_u;
+  // without enriched cells only the regular kernels run and nq_wn is irrelevant
+  const bool any_w = m->nenr == 0;
+  const int nqw = m->P.nq_wn;
 #define LAUNCH(KER, pu, pp, q, w, ENRV, grid, lo_, nl_)                                                 \
   hipLaunchKernelGGL((KER<pu, pp, q, w, ENRV>), dim3((unsigned)(grid)), dim3(kDgThreads), 0, s, A, lo_, nl_)
 #define X(pu, pp, q, w)                                                                                  \
-  if (m->np_u == pu && m->np_p == pp && m->P.nq_u == q && nqw == w) {                                     \
+  if (m->np_u == pu && m->np_p == pp && m->P.nq_u == q && (any_w || nqw == w)) {                          \
     if (nreg > 0) {                                                                                      \
       if (divergence) LAUNCH(divergence_kernel, pu, pp, q, q, false, nreg, lo, nl);                       \
       else LAUNCH(gradient_kernel, pu, pp, q, q, false, nreg, lo, nl);                                    \

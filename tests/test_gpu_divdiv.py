@@ -22,6 +22,8 @@ CASES = {
     "k3_plain": MeshConfig(nx=3, ny=3, nz=2, gamma=1.1, k_u=3, nq_u=5, k_p=2, nq_p=3, enrich_lower=0,
                            enrich_upper=0),
     "k2_periodic": MeshConfig(nx=3, ny=3, nz=2, k_u=2, nq_u=4, k_p=1, nq_p=2, fully_periodic=1),
+    # k = 4 without enrichment: nq_wn (8) differs from nq_u (7) and is irrelevant
+    "k4_periodic": MeshConfig(nx=3, ny=3, nz=2, gamma=0.0, k_u=4, nq_u=7, k_p=3, nq_p=4, fully_periodic=1),
 }
 
 
