@@ -32,13 +32,13 @@ def _gl_nodes(n):
     return 0.5 * (np.concatenate([[-1.0], np.sort(np.real(inner)), [1.0]]) + 1.0)
 
 
-def _field(cfg, t):
+def _field(cfg, t, amp=1.0):
     """Exact nodal velocity at time t (polynomial block; no enrichment)."""
     n = cfg.k_u + 1
     xi = _gl_nodes(n)
     hx, hy = cfg.Lx / cfg.nx, 2.0 / cfg.ny
     a, b = 2.0 * math.pi / cfg.Lx, math.pi
-    decay = math.exp(-cfg.nu * (a * a + b * b) * t)
+    decay = amp * math.exp(-cfg.nu * (a * a + b * b) * t)
     u = np.zeros((cfg.nz, cfg.ny, cfg.nx, 3, n, n, n))       # [ez][ey][ex][c][m][j][i]
     for ey in range(cfg.ny):
         y = -1.0 + (ey + xi) * hy                             # along j
@@ -79,3 +79,34 @@ def test_taylor_green_decay():
     assert np.abs(w).max() <= 5e-3 * np.abs(got).max()
     assert err <= 1e-3
     assert abs(decay / exact_decay - 1.0) <= 1e-3
+
+
+def _run(cfg, dt, nsteps, amp, dt_over_cr):
+    mesh = Mesh(cfg)
+    sp = mesh.step_params(dt, order=2, dt_over_cr=dt_over_cr, poisson=mesh.solve_params(rtol=1e-12, mixed=False),
+                          helmholtz_rtol=1e-12)
+    u_nm1 = torch.tensor(_field(cfg, -dt, amp), device="cuda")
+    u_n = torch.tensor(_field(cfg, 0.0, amp), device="cuda")
+    p = torch.zeros(cfg.n_p, dtype=torch.float64, device="cuda")
+    for _ in range(nsteps):
+        u_np1, p, _ = mesh.dual_splitting_step(sp, u_n, u_nm1, p)
+        u_nm1, u_n = u_n, u_np1
+    got = u_n.cpu().numpy().reshape(cfg.ncell, 3, -1)
+    ref = _field(cfg, nsteps * dt, amp).reshape(cfg.ncell, 3, -1)
+    return float(np.abs(got[:, :2] - ref[:, :2]).max() / np.abs(ref[:, :2]).max())
+
+
+def test_taylor_green_second_order_in_time():
+    """BDF2 with extrapolated convection (Sec. 4.1) is second order in time:
+    at a fixed end time T = 0.8, halving dt cuts the in-plane error about
+    fourfold.  The time error has to dominate, so the decay is fast (nu =
+    0.1), the steps long (dt = 0.1, 0.05) and the amplitude small (0.1, for a
+    Courant number below 0.13 of the explicit convective step); the div-div
+    penalty is off (dt/Cr = 0), since its size follows dt and the spatial
+    divergence error, not the time integration."""
+    cfg = MeshConfig(nx=8, ny=8, nz=1, gamma=0.0, k_u=4, nq_u=7, k_p=3, nq_p=4, fully_periodic=1, nu=0.1)
+    e1 = _run(cfg, 0.1, 8, 0.1, 0.0)
+    e2 = _run(cfg, 0.05, 16, 0.1, 0.0)
+    print(f"[gpu] Taylor-Green in-plane errors at T = 0.8: dt 0.1 {e1:.3e}, dt 0.05 {e2:.3e}, ratio {e1 / e2:.2f}",
+          flush=True)
+    assert e1 / e2 >= 3.4
