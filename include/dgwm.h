@@ -439,6 +439,7 @@ typedef struct {
   int32_t iterations, restarts;
   double rel_resid;     /* final ||gamma b - H x|| / ||gamma b||                                       */
   double seconds;       /* host wall time of the call                                                  */
+  int32_t reorthogonalised; /* Arnoldi steps whose Gram-Schmidt projection was repeated                */
 } dg_gmres_stats;
 
 /* Device workspace of dg_solve_helmholtz: restart + 1 velocity vectors plus
@@ -454,13 +455,16 @@ int64_t dg_helmholtz_workspace_bytes(const dg_mesh* mesh, const dg_gmres_params*
  * as H x = gamma x + M^{-1} A x = gamma b (gamma = gamma0/dt) by restarted
  * GMRES in FP64 (the paper solves this step with GMRES, Sec. 5.1): the
  * cell-wise M^{-1} of dg_apply_inverse_mass is the left preconditioner, and
- * the residual is measured in that preconditioned form.  Modified
- * Gram-Schmidt with the projections kept on the device, one host read-back
- * per Arnoldi step, deterministic reductions; convergence is confirmed with
- * the true residual.
+ * the residual is measured in that preconditioned form.  The Arnoldi
+ * process runs on M^{-1} A (the same Krylov spaces; gamma is added to the
+ * Hessenberg diagonal), orthogonalised by classical Gram-Schmidt over all
+ * previous vectors at once and repeated when the projection removes more
+ * than half of the vector's squared norm; the projections stay on the device, one host
+ * read-back per Arnoldi step (two with the repeat), deterministic
+ * reductions; convergence is confirmed with the true residual.
  *   nut: device, from dg_eddy_viscosity (may be NULL without enriched cells);
  *   b, x: device, dg_num_dofs(mesh, 0) doubles, distinct; x holds the
- *   initial guess (e.g. b); ws: >= dg_helmholtz_workspace_bytes.
+ *   initial guess (e.g. b); ws: device, 256-byte aligned, >= dg_helmholtz_workspace_bytes.
  *   Errors: DG_ERR_ARG, DG_ERR_WORKSPACE, DG_ERR_UNSUPPORTED (curved wall),
  *   DG_ERR_NONFINITE, DG_ERR_NOT_CONVERGED (stats filled), DG_ERR_HIP. */
 int dg_solve_helmholtz(const dg_mesh* mesh, const double* nut, double gamma0_over_dt, const double* b, double* x,

@@ -9,11 +9,19 @@
 // small time steps of the explicit convective step; the paper solves this
 // step with GMRES (Sec. 5.1 reports its iteration counts).
 //
-// Arnoldi with modified Gram-Schmidt; every scalar of an Arnoldi step stays
-// on the device (the projections are subtracted with their device values) and
-// one copy per step brings the new Hessenberg column to the host, where the
-// Givens rotations and the least-squares solution live.  Reductions are
-// two-stage fixed-grid sums (deterministic).
+// The Arnoldi process runs on K = M^{-1} A instead of H = gamma I + K: both
+// span the same Krylov spaces, and the Hessenberg matrix of H is that of K
+// with gamma added to its diagonal.  This keeps the dominant gamma v_j out of
+// the new vector, so its projections do not cancel.  Orthogonalisation is
+// classical Gram-Schmidt over all previous basis vectors at once (one pass
+// computes every projection, one pass subtracts them and forms the norm),
+// repeated once when the norm drops below 1/sqrt(2) of its value before the
+// projection (the test of Daniel, Gragg, Kaufman and Stewart, 1976).  Every
+// scalar of an Arnoldi step stays on the device (the projections are
+// subtracted with their device values) and one copy per step (two with the
+// repeat) brings the new Hessenberg column to the host, where the Givens
+// rotations and the least-squares solution live.  Reductions are two-stage
+// fixed-grid sums (deterministic).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -27,8 +35,15 @@ namespace {
 
 constexpr int kHThreads = 256;
 constexpr int kHMaxParts = 1024;
-constexpr int kHScalars = 128;  // device scalars: Hessenberg column (<= restart + 1), norms
 constexpr int kHMaxRestart = 100;
+constexpr int kHChunk = 16;      // basis vectors per pass of the multi-vector kernels
+// device scalars: the first and the repeated projections of a Hessenberg
+// column with their norms (kHPass2 apart), ||w||^2 before the projection,
+// ||gamma b||^2 and ||gamma b||
+constexpr int kHPass2 = 104;
+constexpr int kHScalars = 256;
+constexpr int kHSlotW = kHScalars - 3;
+constexpr int kHRows = kHMaxRestart + 2;  // rows of reduction partials
 
 int h_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, kHMaxParts)); }
 unsigned ew_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
@@ -69,12 +84,105 @@ __global__ __launch_bounds__(kHThreads) void h_final(const double* __restrict__ 
   }
 }
 
-// w -= (*h) v
-__global__ void h_sub_proj(double* __restrict__ w, const double* __restrict__ v, int64_t n,
-                           const double* __restrict__ h) {
-  const double c = *h;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    w[i] -= c * v[i];
+// Projections of w on nk <= kHChunk basis vectors V_k0 .. V_{k0+nk-1} in one
+// pass: part[(k0 + k) nbp + b] = block b's partial sum of V_{k0+k} . w, and
+// with ww also part[(kHRows - 1) nbp + b] = its partial sum of w . w.
+__global__ __launch_bounds__(kHThreads) void h_mdot(const double* __restrict__ V, int64_t stride, int k0, int nk,
+                                                    const double* __restrict__ w, int64_t n, double* __restrict__ part,
+                                                    int nbp, int ww) {
+  __shared__ double sh[(kHChunk + 1) * (kHThreads / 64)];
+  double acc[kHChunk + 1];
+#pragma unroll
+  for (int k = 0; k <= kHChunk; ++k) acc[k] = 0.0;
+  const double* v0 = V + (int64_t)k0 * stride;
+  // pairs of entries (16-byte accesses; vectors start 256 bytes apart), then an odd last entry
+  const int64_t n2 = n >> 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 wi = reinterpret_cast<const double2*>(w)[i];
+#pragma unroll
+    for (int k = 0; k < kHChunk; ++k)
+      if (k < nk) {
+        const double2 v = reinterpret_cast<const double2*>(v0 + k * stride)[i];
+        acc[k] += v.x * wi.x + v.y * wi.y;
+      }
+    if (ww) acc[kHChunk] += wi.x * wi.x + wi.y * wi.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double wi = w[n - 1];
+#pragma unroll
+    for (int k = 0; k < kHChunk; ++k)
+      if (k < nk) acc[k] += v0[k * stride + n - 1] * wi;
+    if (ww) acc[kHChunk] += wi * wi;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k <= kHChunk; ++k) {
+    double x = acc[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) sh[k * (kHThreads / 64) + wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x <= kHChunk) {
+    const int k = threadIdx.x;
+    double x = 0.0;
+    for (int i = 0; i < kHThreads / 64; ++i) x += sh[k * (kHThreads / 64) + i];
+    if (k < nk) part[(int64_t)(k0 + k) * nbp + blockIdx.x] = x;
+    else if (k == kHChunk && ww) part[(int64_t)(kHRows - 1) * nbp + blockIdx.x] = x;
+  }
+}
+
+// out[k] = sum of the nb partials of row row0 + k (workgroup k, fixed order);
+// with sq >= 0, out[sq] = sqrt(out[k_sq]) for the row k_sq = sq - 1.
+__global__ __launch_bounds__(kHThreads) void h_mfinal(const double* __restrict__ part, int nbp, int nb, int row0,
+                                                      double* __restrict__ out, int sq) {
+  __shared__ double sh[kHThreads / 64];
+  const double* p = part + (int64_t)(row0 + blockIdx.x) * nbp;
+  double v = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += p[i];
+  v = h_block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    out[blockIdx.x] = v;
+    if (sq >= 0 && (int)blockIdx.x == sq - 1) out[sq] = sqrt(v);
+  }
+}
+
+// w -= sum_{k < nk} h_k V_{k0+k} in one pass (h on the device); with nrm,
+// part[b] = block b's partial sum of the new w . w.
+__global__ __launch_bounds__(kHThreads) void h_mupdate(double* __restrict__ w, const double* __restrict__ V,
+                                                       int64_t stride, int k0, int nk, const double* __restrict__ h,
+                                                       int64_t n, double* __restrict__ part, int nrm) {
+  __shared__ double sh[kHThreads / 64];
+  double c[kHChunk];
+#pragma unroll
+  for (int k = 0; k < kHChunk; ++k) c[k] = k < nk ? h[k] : 0.0;
+  const double* v0 = V + (int64_t)k0 * stride;
+  double q = 0.0;
+  const int64_t n2 = n >> 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 x = reinterpret_cast<const double2*>(w)[i];
+#pragma unroll
+    for (int k = 0; k < kHChunk; ++k)
+      if (k < nk) {
+        const double2 v = reinterpret_cast<const double2*>(v0 + k * stride)[i];
+        x.x -= c[k] * v.x;
+        x.y -= c[k] * v.y;
+      }
+    reinterpret_cast<double2*>(w)[i] = x;
+    q += x.x * x.x + x.y * x.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double x = w[n - 1];
+#pragma unroll
+    for (int k = 0; k < kHChunk; ++k)
+      if (k < nk) x -= c[k] * v0[k * stride + n - 1];
+    w[n - 1] = x;
+    q += x * x;
+  }
+  if (nrm) {
+    q = h_block_sum(q, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = q;
+  }
 }
 
 // w = w / (*nrm)
@@ -82,12 +190,6 @@ __global__ void h_normalise(double* __restrict__ w, int64_t n, const double* __r
   const double s = 1.0 / *nrm;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     w[i] *= s;
-}
-
-// y = g x + y  (the operator's gamma x term on top of M^{-1} A x)
-__global__ void h_add_scaled(double* __restrict__ y, const double* __restrict__ x, int64_t n, double g) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += g * x[i];
 }
 
 __global__ void h_zero(double* __restrict__ x, int64_t n) {
@@ -130,13 +232,39 @@ struct Gm {
   double gamma;
 
   double* v(int k) const { return V + k * stride; }
-  // y = H x = gamma x + M^{-1} A x  (y != x)
-  int apply(const double* x, double* y) {
+  // y = K x = M^{-1} A x  (y != x)
+  int apply_k(const double* x, double* y) {
     int rc = launch_viscous_multiscale(m, nut, x, y, s);
     if (!rc) rc = launch_inverse_mass(m, y, y, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(h_add_scaled, dim3(ew_blocks(n)), dim3(256), 0, s, y, x, n, gamma);
-    return check_hip(hipGetLastError(), "helmholtz operator");
+    return rc;
+  }
+  // sc[o + k] = V_k . w for k <= j; with ww also sc[kHSlotW] = w . w
+  int proj_dots(const double* w, int j, int o, bool ww) {
+    const int nb = h_blocks(n);
+    for (int k0 = 0; k0 <= j; k0 += kHChunk) {
+      const int nk = std::min(kHChunk, j + 1 - k0);
+      hipLaunchKernelGGL(h_mdot, dim3(nb), dim3(kHThreads), 0, s, V, stride, k0, nk, w, n, part, kHMaxParts,
+                         (ww && k0 == 0) ? 1 : 0);
+    }
+    hipLaunchKernelGGL(h_mfinal, dim3(j + 1), dim3(kHThreads), 0, s, part, kHMaxParts, nb, 0, sc + o, -1);
+    if (ww)
+      hipLaunchKernelGGL(h_mfinal, dim3(1), dim3(kHThreads), 0, s, part, kHMaxParts, nb, kHRows - 1, sc + kHSlotW,
+                         -1);
+    return check_hip(hipGetLastError(), "helmholtz projections");
+  }
+  // w -= sum_k sc[o + k] V_k (k <= j); sc[o + j + 1] = ||w||^2, sc[o + j + 2] = ||w||
+  int proj_update(double* w, int j, int o) {
+    const int nb = h_blocks(n);
+    for (int k0 = 0; k0 <= j; k0 += kHChunk) {
+      const int nk = std::min(kHChunk, j + 1 - k0);
+      hipLaunchKernelGGL(h_mupdate, dim3(nb), dim3(kHThreads), 0, s, w, V, stride, k0, nk, sc + o + k0, n, part,
+                         (k0 + nk > j) ? 1 : 0);
+    }
+    hipLaunchKernelGGL(h_mfinal, dim3(1), dim3(kHThreads), 0, s, part, kHMaxParts, nb, 0, sc + o + j + 1, 1);
+    return check_hip(hipGetLastError(), "helmholtz projection update");
+  }
+  int fetch(double* h, int o, int cnt) {
+    return check_hip(hipMemcpyAsync(h, sc + o, sizeof(double) * cnt, hipMemcpyDeviceToHost, s), "read-back");
   }
   // sc[o] = a.b (and sc[o2] = sqrt of it if o2 >= 0)
   int dot(const double* a, const double* b, int o, int o2 = -1) {
@@ -157,18 +285,20 @@ struct Gm {
 int64_t helmholtz_workspace_bytes(const dg_mesh* m, int restart) {
   const size_t vec = up256(sizeof(double) * (size_t)m->n_vel);
   return (int64_t)((size_t)(restart + 1) * vec + up256(sizeof(double) * kHScalars) +
-                   up256(sizeof(double) * kHMaxParts));
+                   up256(sizeof(double) * kHRows * kHMaxParts));
 }
 
 int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const double* b, double* x, double rtol,
                     int max_iter, int restart, void* ws, size_t ws_bytes, dg_gmres_stats* st, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (restart < 1 || restart > kHMaxRestart || restart + 2 > kHScalars)
+  if (restart < 1 || restart > kHMaxRestart)
     return set_error(DG_ERR_ARG, "GMRES restart length outside [1, 100]");
   if (!(rtol > 0) || max_iter < 1 || !(gamma > 0) || !std::isfinite(gamma))
     return set_error(DG_ERR_ARG, "invalid Helmholtz/GMRES parameters");
   if ((int64_t)ws_bytes < helmholtz_workspace_bytes(m, restart))
     return set_error(DG_ERR_WORKSPACE, "Helmholtz workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) & 255u)  // the Krylov kernels read 16-byte pairs
+    return set_error(DG_ERR_ARG, "Helmholtz workspace must be 256-byte aligned");
   Gm G;
   G.m = m;
   G.nut = nut;
@@ -195,7 +325,9 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
   }
   int it = 0, restarts = 0;
   double rel = 1.0;
-  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h(restart + 2);
+  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h(restart + 2),
+      h2(restart + 2);
+  int reorth = 0;
   bool converged = false;
   while (!converged && it < max_iter) {
     // r = gamma b - H x into V_0, beta = ||r||
@@ -218,18 +350,30 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
     int j = 0;
     for (; j < restart && it < max_iter; ++j, ++it) {
       double* w = G.v(j + 1);
-      if ((rc = G.apply(G.v(j), w))) return rc;
-      for (int k = 0; k <= j; ++k) {  // modified Gram-Schmidt, scalars on the device
-        if ((rc = G.dot(G.v(k), w, k))) return rc;
-        hipLaunchKernelGGL(h_sub_proj, dim3(ew_blocks(G.n)), dim3(256), 0, s, w, G.v(k), G.n, G.sc + k);
+      if ((rc = G.apply_k(G.v(j), w))) return rc;
+      // classical Gram-Schmidt against V_0 .. V_j, scalars on the device
+      if ((rc = G.proj_dots(w, j, 0, true))) return rc;
+      if ((rc = G.proj_update(w, j, 0))) return rc;
+      double w2 = 0.0;  // ||w||^2 before the projection
+      if ((rc = G.fetch(h.data(), 0, j + 3)) || (rc = G.fetch(&w2, kHSlotW, 1))) return rc;
+      if ((rc = check_hip(hipStreamSynchronize(s), "read-back wait"))) return rc;
+      double hn = h[j + 2];  // ||w|| after the projection
+      int slot = j + 2;
+      if (!(hn >= std::sqrt(0.5 * w2))) {  // most of w was removed: project once more
+        if ((rc = G.proj_dots(w, j, kHPass2, false))) return rc;
+        if ((rc = G.proj_update(w, j, kHPass2))) return rc;
+        if ((rc = G.read(h2.data(), kHPass2, j + 3))) return rc;
+        for (int k = 0; k <= j; ++k) h[k] += h2[k];
+        hn = h2[j + 2];
+        slot = kHPass2 + j + 2;
+        ++reorth;
       }
-      if ((rc = G.dot(w, w, j + 1, j + 2))) return rc;
-      if ((rc = G.read(h.data(), 0, j + 3))) return rc;
-      const double hn = h[j + 2];  // ||w||
       if (!std::isfinite(hn)) return set_error(DG_ERR_NONFINITE, "non-finite Arnoldi vector");
-      if (hn > 0) hipLaunchKernelGGL(h_normalise, dim3(ew_blocks(G.n)), dim3(256), 0, s, w, G.n, G.sc + j + 2);
-      // Hessenberg column j: h[0..j], hn; apply the previous rotations, then a new one
+      if (hn > 0) hipLaunchKernelGGL(h_normalise, dim3(ew_blocks(G.n)), dim3(256), 0, s, w, G.n, G.sc + slot);
+      // Hessenberg column j of H = gamma I + K: h[0..j] (+ gamma on the diagonal), hn; apply the previous
+      // rotations, then a new one
       for (int k = 0; k <= j; ++k) H[(size_t)k * restart + j] = h[k];
+      H[(size_t)j * restart + j] += gamma;
       H[(size_t)(j + 1) * restart + j] = hn;
       for (int k = 0; k < j; ++k) {
         const double a = H[(size_t)k * restart + j], c = H[(size_t)(k + 1) * restart + j];
@@ -281,6 +425,7 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
   }
   stats.iterations = it;
   stats.restarts = restarts;
+  stats.reorthogonalised = reorth;
   stats.rel_resid = rel;
   stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (st) *st = stats;
