@@ -467,7 +467,6 @@ def main():
         extras["dual_splitting_step"] = {
             "median_s": float(np.median(step_t)), "poisson_its": step_st.poisson.outer_its,
             "poisson_rel_resid": step_st.poisson.rel_resid, "helmholtz_its": step_st.helmholtz.iterations,
-            "helmholtz_repeated_projections": step_st.helmholtz.reorthogonalised,
             "helmholtz_s": step_st.helmholtz.seconds,
             "helmholtz_rel_resid": step_st.helmholtz.rel_resid, "dt": 1e-3, "order": 2,
             "velocity_dofs": n_vel, "pressure_dofs": n_p}

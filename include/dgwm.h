@@ -439,7 +439,6 @@ typedef struct {
   int32_t iterations, restarts;
   double rel_resid;     /* final ||gamma b - H x|| / ||gamma b||                                       */
   double seconds;       /* host wall time of the call                                                  */
-  int32_t reorthogonalised; /* Arnoldi steps whose Gram-Schmidt projection was repeated                */
 } dg_gmres_stats;
 
 /* Device workspace of dg_solve_helmholtz: restart + 1 velocity vectors plus
@@ -457,11 +456,11 @@ int64_t dg_helmholtz_workspace_bytes(const dg_mesh* mesh, const dg_gmres_params*
  * cell-wise M^{-1} of dg_apply_inverse_mass is the left preconditioner, and
  * the residual is measured in that preconditioned form.  The Arnoldi
  * process runs on M^{-1} A (the same Krylov spaces; gamma is added to the
- * Hessenberg diagonal), orthogonalised by classical Gram-Schmidt over all
- * previous vectors at once and repeated when the projection removes more
- * than half of the vector's squared norm; the projections stay on the device, one host
- * read-back per Arnoldi step (two with the repeat), deterministic
- * reductions; convergence is confirmed with the true residual.
+ * Hessenberg diagonal), orthogonalised by classical Gram-Schmidt applied
+ * twice with the second pass delayed into the next step (two passes over
+ * the basis per step); the projections stay on the device, one host
+ * read-back per Arnoldi step, deterministic reductions; convergence is
+ * confirmed with the true residual.
  *   nut: device, from dg_eddy_viscosity (may be NULL without enriched cells);
  *   b, x: device, dg_num_dofs(mesh, 0) doubles, distinct; x holds the
  *   initial guess (e.g. b); ws: device, 256-byte aligned, >= dg_helmholtz_workspace_bytes.

@@ -51,7 +51,7 @@ class GmresParams(ctypes.Structure):
 
 class GmresStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_resid", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("reorthogonalised", ctypes.c_int32)]
+                ("seconds", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):

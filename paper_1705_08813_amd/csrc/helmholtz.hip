@@ -11,17 +11,20 @@
 //
 // The Arnoldi process runs on K = M^{-1} A instead of H = gamma I + K: both
 // span the same Krylov spaces, and the Hessenberg matrix of H is that of K
-// with gamma added to its diagonal.  This keeps the dominant gamma v_j out of
-// the new vector, so its projections do not cancel.  Orthogonalisation is
-// classical Gram-Schmidt over all previous basis vectors at once (one pass
-// computes every projection, one pass subtracts them and forms the norm),
-// repeated once when the norm drops below 1/sqrt(2) of its value before the
-// projection (the test of Daniel, Gragg, Kaufman and Stewart, 1976).  Every
-// scalar of an Arnoldi step stays on the device (the projections are
-// subtracted with their device values) and one copy per step (two with the
-// repeat) brings the new Hessenberg column to the host, where the Givens
-// rotations and the least-squares solution live.  Reductions are two-stage
-// fixed-grid sums (deterministic).
+// with gamma added to its diagonal, which keeps the dominant gamma v_j out of
+// the projections.  Orthogonalisation is classical Gram-Schmidt applied twice,
+// the second pass delayed into the next Arnoldi step (the DCGS2 scheme of
+// Swirydowicz, Langou, Ananthan, Yang and Thomas, 2021, here derived for the
+// host-side Hessenberg bookkeeping below): step j applies K to the candidate
+// u_j (projected once, not normalised), one read pass over the basis gives the
+// projections of both u_j and w = K u_j, and one write pass finishes v_j
+// (second projection and normalisation) and forms the once-projected
+// candidate u_{j+1}.  The basis vectors are read twice per step instead of
+// four (twice-applied classical) or five (modified Gram-Schmidt) times.  Every
+// projection coefficient stays on the device (the updates read them there);
+// one copy per step brings them to the host, where the Hessenberg matrix, the
+// Givens rotations and the least-squares solution live.  Reductions are
+// two-stage fixed-grid sums (deterministic).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -36,14 +39,14 @@ namespace {
 constexpr int kHThreads = 256;
 constexpr int kHMaxParts = 1024;
 constexpr int kHMaxRestart = 100;
-constexpr int kHChunk = 16;      // basis vectors per pass of the multi-vector kernels
-// device scalars: the first and the repeated projections of a Hessenberg
-// column with their norms (kHPass2 apart), ||w||^2 before the projection,
-// ||gamma b||^2 and ||gamma b||
-constexpr int kHPass2 = 104;
+constexpr int kHChunk = 16;      // basis vectors per pass of the Krylov kernels
+// device scalars: projections of the candidate (s, from 0) and of the new
+// vector (z, from kHZ), u.u and u.w (kHSlotA, +1), ||gamma b||^2 and ||gamma b||
+constexpr int kHZ = 104;
 constexpr int kHScalars = 256;
-constexpr int kHSlotW = kHScalars - 3;
-constexpr int kHRows = kHMaxRestart + 2;  // rows of reduction partials
+constexpr int kHSlotA = kHScalars - 6;
+// rows of reduction partials: s, then z, then u.u and u.w
+constexpr int kHRowZ = kHMaxRestart, kHRowA = 2 * kHMaxRestart, kHRows = 2 * kHMaxRestart + 2;
 
 int h_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, kHMaxParts)); }
 unsigned ew_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
@@ -84,51 +87,64 @@ __global__ __launch_bounds__(kHThreads) void h_final(const double* __restrict__ 
   }
 }
 
-// Projections of w on nk <= kHChunk basis vectors V_k0 .. V_{k0+nk-1} in one
-// pass: part[(k0 + k) nbp + b] = block b's partial sum of V_{k0+k} . w, and
-// with ww also part[(kHRows - 1) nbp + b] = its partial sum of w . w.
-__global__ __launch_bounds__(kHThreads) void h_mdot(const double* __restrict__ V, int64_t stride, int k0, int nk,
-                                                    const double* __restrict__ w, int64_t n, double* __restrict__ part,
-                                                    int nbp, int ww) {
-  __shared__ double sh[(kHChunk + 1) * (kHThreads / 64)];
-  double acc[kHChunk + 1];
+// One read pass over nk <= kHChunk basis vectors V_k0 .. V_{k0+nk-1}, the
+// candidate u and (hw) the new vector w: block b's partial sums of V_k . u
+// (row k0 + k), V_k . w (row kHRowZ + k0 + k) and, with first, u . u and
+// u . w (rows kHRowA, kHRowA + 1).
+__global__ __launch_bounds__(kHThreads) void h_ddot(const double* __restrict__ V, int64_t stride, int k0, int nk,
+                                                    const double* __restrict__ u, const double* __restrict__ w,
+                                                    int hw, int64_t n, double* __restrict__ part, int nbp, int first) {
+  constexpr int NA = 2 * kHChunk + 2, NW = kHThreads / 64;
+  __shared__ double sh[NA * NW];
+  double as[kHChunk], az[kHChunk], aa = 0.0, at = 0.0;
 #pragma unroll
-  for (int k = 0; k <= kHChunk; ++k) acc[k] = 0.0;
+  for (int k = 0; k < kHChunk; ++k) as[k] = az[k] = 0.0;
   const double* v0 = V + (int64_t)k0 * stride;
   // pairs of entries (16-byte accesses; vectors start 256 bytes apart), then an odd last entry
   const int64_t n2 = n >> 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 wi = reinterpret_cast<const double2*>(w)[i];
+    const double2 ui = reinterpret_cast<const double2*>(u)[i];
+    const double2 wi = hw ? reinterpret_cast<const double2*>(w)[i] : double2{0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < kHChunk; ++k)
       if (k < nk) {
         const double2 v = reinterpret_cast<const double2*>(v0 + k * stride)[i];
-        acc[k] += v.x * wi.x + v.y * wi.y;
+        as[k] += v.x * ui.x + v.y * ui.y;
+        az[k] += v.x * wi.x + v.y * wi.y;
       }
-    if (ww) acc[kHChunk] += wi.x * wi.x + wi.y * wi.y;
+    aa += ui.x * ui.x + ui.y * ui.y;
+    at += ui.x * wi.x + ui.y * wi.y;
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    const double wi = w[n - 1];
+    const double ui = u[n - 1], wi = hw ? w[n - 1] : 0.0;
 #pragma unroll
     for (int k = 0; k < kHChunk; ++k)
-      if (k < nk) acc[k] += v0[k * stride + n - 1] * wi;
-    if (ww) acc[kHChunk] += wi * wi;
+      if (k < nk) {
+        const double v = v0[k * stride + n - 1];
+        as[k] += v * ui;
+        az[k] += v * wi;
+      }
+    aa += ui * ui;
+    at += ui * wi;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k <= kHChunk; ++k) {
-    double x = acc[k];
+  for (int q = 0; q < NA; ++q) {
+    double x = q < kHChunk ? as[q] : (q < 2 * kHChunk ? az[q - kHChunk] : (q == 2 * kHChunk ? aa : at));
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) sh[k * (kHThreads / 64) + wv] = x;
+    if (lane == 0) sh[q * NW + wv] = x;
   }
   __syncthreads();
-  if (threadIdx.x <= kHChunk) {
-    const int k = threadIdx.x;
+  if (threadIdx.x < NA) {
+    const int q = threadIdx.x;
     double x = 0.0;
-    for (int i = 0; i < kHThreads / 64; ++i) x += sh[k * (kHThreads / 64) + i];
-    if (k < nk) part[(int64_t)(k0 + k) * nbp + blockIdx.x] = x;
-    else if (k == kHChunk && ww) part[(int64_t)(kHRows - 1) * nbp + blockIdx.x] = x;
+    for (int i = 0; i < NW; ++i) x += sh[q * NW + i];
+    int row = -1;
+    if (q < kHChunk) row = q < nk ? k0 + q : -1;
+    else if (q < 2 * kHChunk) row = (hw && q - kHChunk < nk) ? kHRowZ + k0 + q - kHChunk : -1;
+    else if (first) row = kHRowA + (q - 2 * kHChunk);
+    if (row >= 0) part[(int64_t)row * nbp + blockIdx.x] = x;
   }
 }
 
@@ -147,41 +163,58 @@ __global__ __launch_bounds__(kHThreads) void h_mfinal(const double* __restrict__
   }
 }
 
-// w -= sum_{k < nk} h_k V_{k0+k} in one pass (h on the device); with nrm,
-// part[b] = block b's partial sum of the new w . w.
-__global__ __launch_bounds__(kHThreads) void h_mupdate(double* __restrict__ w, const double* __restrict__ V,
-                                                       int64_t stride, int k0, int nk, const double* __restrict__ h,
-                                                       int64_t n, double* __restrict__ part, int nrm) {
-  __shared__ double sh[kHThreads / 64];
-  double c[kHChunk];
+// One write pass over a chunk of the basis: u -= sum_k s_k V_{k0+k} and
+// (hw) w -= sum_k z_k V_{k0+k}, with s and z on the device; in the last chunk
+// also u = u / beta (the finished basis vector v_j) and w = w / beta - g2 u
+// (the next candidate; ib = 1 / beta).
+__global__ __launch_bounds__(kHThreads) void h_dupdate(double* __restrict__ u, double* __restrict__ w, int hw,
+                                                       const double* __restrict__ V, int64_t stride, int k0, int nk,
+                                                       const double* __restrict__ sv, const double* __restrict__ zv,
+                                                       int64_t n, int last, double ib, double g2) {
+  double cs[kHChunk], cz[kHChunk];
 #pragma unroll
-  for (int k = 0; k < kHChunk; ++k) c[k] = k < nk ? h[k] : 0.0;
+  for (int k = 0; k < kHChunk; ++k) {
+    cs[k] = k < nk ? sv[k0 + k] : 0.0;
+    cz[k] = (hw && k < nk) ? zv[k0 + k] : 0.0;
+  }
   const double* v0 = V + (int64_t)k0 * stride;
-  double q = 0.0;
   const int64_t n2 = n >> 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
-    double2 x = reinterpret_cast<const double2*>(w)[i];
+    double2 a = reinterpret_cast<const double2*>(u)[i];
+    double2 c = hw ? reinterpret_cast<const double2*>(w)[i] : double2{0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < kHChunk; ++k)
       if (k < nk) {
         const double2 v = reinterpret_cast<const double2*>(v0 + k * stride)[i];
-        x.x -= c[k] * v.x;
-        x.y -= c[k] * v.y;
+        a.x -= cs[k] * v.x;
+        a.y -= cs[k] * v.y;
+        c.x -= cz[k] * v.x;
+        c.y -= cz[k] * v.y;
       }
-    reinterpret_cast<double2*>(w)[i] = x;
-    q += x.x * x.x + x.y * x.y;
+    if (last) {
+      a.x *= ib;
+      a.y *= ib;
+      c.x = c.x * ib - g2 * a.x;
+      c.y = c.y * ib - g2 * a.y;
+    }
+    reinterpret_cast<double2*>(u)[i] = a;
+    if (hw) reinterpret_cast<double2*>(w)[i] = c;
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    double x = w[n - 1];
+    double a = u[n - 1], c = hw ? w[n - 1] : 0.0;
 #pragma unroll
     for (int k = 0; k < kHChunk; ++k)
-      if (k < nk) x -= c[k] * v0[k * stride + n - 1];
-    w[n - 1] = x;
-    q += x * x;
-  }
-  if (nrm) {
-    q = h_block_sum(q, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = q;
+      if (k < nk) {
+        const double v = v0[k * stride + n - 1];
+        a -= cs[k] * v;
+        c -= cz[k] * v;
+      }
+    if (last) {
+      a *= ib;
+      c = c * ib - g2 * a;
+    }
+    u[n - 1] = a;
+    if (hw) w[n - 1] = c;
   }
 }
 
@@ -238,29 +271,32 @@ struct Gm {
     if (!rc) rc = launch_inverse_mass(m, y, y, s);
     return rc;
   }
-  // sc[o + k] = V_k . w for k <= j; with ww also sc[kHSlotW] = w . w
-  int proj_dots(const double* w, int j, int o, bool ww) {
+  // projections of the candidate u = V_j on V_0 .. V_{j-1} into sc[0 ..] and, with w, of w into sc[kHZ ..];
+  // u.u and u.w into sc[kHSlotA], sc[kHSlotA + 1]
+  int ddots(int j, const double* w) {
     const int nb = h_blocks(n);
-    for (int k0 = 0; k0 <= j; k0 += kHChunk) {
-      const int nk = std::min(kHChunk, j + 1 - k0);
-      hipLaunchKernelGGL(h_mdot, dim3(nb), dim3(kHThreads), 0, s, V, stride, k0, nk, w, n, part, kHMaxParts,
-                         (ww && k0 == 0) ? 1 : 0);
+    const double* u = v(j);
+    for (int k0 = 0; k0 == 0 || k0 < j; k0 += kHChunk) {
+      const int nk = std::min(kHChunk, j - k0);
+      hipLaunchKernelGGL(h_ddot, dim3(nb), dim3(kHThreads), 0, s, V, stride, k0, nk, u, w, w ? 1 : 0, n, part,
+                         kHMaxParts, k0 == 0 ? 1 : 0);
     }
-    hipLaunchKernelGGL(h_mfinal, dim3(j + 1), dim3(kHThreads), 0, s, part, kHMaxParts, nb, 0, sc + o, -1);
-    if (ww)
-      hipLaunchKernelGGL(h_mfinal, dim3(1), dim3(kHThreads), 0, s, part, kHMaxParts, nb, kHRows - 1, sc + kHSlotW,
-                         -1);
+    if (j > 0) {
+      hipLaunchKernelGGL(h_mfinal, dim3(j), dim3(kHThreads), 0, s, part, kHMaxParts, nb, 0, sc, -1);
+      if (w) hipLaunchKernelGGL(h_mfinal, dim3(j), dim3(kHThreads), 0, s, part, kHMaxParts, nb, kHRowZ, sc + kHZ, -1);
+    }
+    hipLaunchKernelGGL(h_mfinal, dim3(2), dim3(kHThreads), 0, s, part, kHMaxParts, nb, kHRowA, sc + kHSlotA, -1);
     return check_hip(hipGetLastError(), "helmholtz projections");
   }
-  // w -= sum_k sc[o + k] V_k (k <= j); sc[o + j + 1] = ||w||^2, sc[o + j + 2] = ||w||
-  int proj_update(double* w, int j, int o) {
-    const int nb = h_blocks(n);
-    for (int k0 = 0; k0 <= j; k0 += kHChunk) {
-      const int nk = std::min(kHChunk, j + 1 - k0);
-      hipLaunchKernelGGL(h_mupdate, dim3(nb), dim3(kHThreads), 0, s, w, V, stride, k0, nk, sc + o + k0, n, part,
-                         (k0 + nk > j) ? 1 : 0);
+  // V_j = (V_j - sum_k s_k V_k) / beta and V_{j+1} = (V_{j+1} - sum_k z_k V_k) / beta - g2 V_j (k < j)
+  int dupdate(int j, bool hw, double ib, double g2) {
+    double* u = v(j);
+    double* w = hw ? v(j + 1) : nullptr;
+    for (int k0 = 0; k0 == 0 || k0 < j; k0 += kHChunk) {
+      const int nk = std::min(kHChunk, j - k0);
+      hipLaunchKernelGGL(h_dupdate, dim3(h_blocks(n)), dim3(kHThreads), 0, s, u, w, hw ? 1 : 0, V, stride, k0, nk,
+                         sc, sc + kHZ, n, (k0 + kHChunk >= j) ? 1 : 0, ib, g2);
     }
-    hipLaunchKernelGGL(h_mfinal, dim3(1), dim3(kHThreads), 0, s, part, kHMaxParts, nb, 0, sc + o + j + 1, 1);
     return check_hip(hipGetLastError(), "helmholtz projection update");
   }
   int fetch(double* h, int o, int cnt) {
@@ -325,9 +361,11 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
   }
   int it = 0, restarts = 0;
   double rel = 1.0;
-  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h(restart + 2),
-      h2(restart + 2);
-  int reorth = 0;
+  // HK: Hessenberg matrix of K (unrotated, row-major with row length restart); R: that of H = gamma I + K after
+  // the Givens rotations; g: the rotated right-hand side
+  const size_t ld = (size_t)restart;
+  std::vector<double> HK((restart + 1) * ld), R((restart + 1) * ld), cs(restart), sn(restart), g(restart + 1),
+      sv(restart + 1), zv(restart + 1), y(restart + 1);
   bool converged = false;
   while (!converged && it < max_iter) {
     // r = gamma b - H x into V_0, beta = ||r||
@@ -346,63 +384,81 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
     }
     hipLaunchKernelGGL(h_normalise, dim3(ew_blocks(G.n)), dim3(256), 0, s, r, G.n, G.sc + 1);
     std::fill(g.begin(), g.end(), 0.0);
+    std::fill(HK.begin(), HK.end(), 0.0);
     g[0] = beta;
-    int j = 0;
-    for (; j < restart && it < max_iter; ++j, ++it) {
-      double* w = G.v(j + 1);
-      if ((rc = G.apply_k(G.v(j), w))) return rc;
-      // classical Gram-Schmidt against V_0 .. V_j, scalars on the device
-      if ((rc = G.proj_dots(w, j, 0, true))) return rc;
-      if ((rc = G.proj_update(w, j, 0))) return rc;
-      double w2 = 0.0;  // ||w||^2 before the projection
-      if ((rc = G.fetch(h.data(), 0, j + 3)) || (rc = G.fetch(&w2, kHSlotW, 1))) return rc;
+    // Step j: V_0 .. V_{j-1} are finished basis vectors, V_j holds the candidate u_j (projected once, not
+    // normalised; for j = 0 the finished v_0).  Columns 0 .. j-2 of HK are final, column j-1 still lacks the
+    // second projection of u_j and its subdiagonal ||u_j - V s||.
+    int j = 0, dim = 0;
+    for (;; ++j) {
+      const bool more = j < restart && it < max_iter;  // another Arnoldi step follows this one
+      double* w = more ? G.v(j + 1) : nullptr;
+      if (more && (rc = G.apply_k(G.v(j), w))) return rc;
+      if ((rc = G.ddots(j, w))) return rc;
+      double au[2] = {0.0, 0.0};  // u.u, u.w
+      if ((j > 0 && (rc = G.fetch(sv.data(), 0, j))) || (more && j > 0 && (rc = G.fetch(zv.data(), kHZ, j))) ||
+          (rc = G.fetch(au, kHSlotA, 2)))
+        return rc;
       if ((rc = check_hip(hipStreamSynchronize(s), "read-back wait"))) return rc;
-      double hn = h[j + 2];  // ||w|| after the projection
-      int slot = j + 2;
-      if (!(hn >= std::sqrt(0.5 * w2))) {  // most of w was removed: project once more
-        if ((rc = G.proj_dots(w, j, kHPass2, false))) return rc;
-        if ((rc = G.proj_update(w, j, kHPass2))) return rc;
-        if ((rc = G.read(h2.data(), kHPass2, j + 3))) return rc;
-        for (int k = 0; k <= j; ++k) h[k] += h2[k];
-        hn = h2[j + 2];
-        slot = kHPass2 + j + 2;
-        ++reorth;
-      }
-      if (!std::isfinite(hn)) return set_error(DG_ERR_NONFINITE, "non-finite Arnoldi vector");
-      if (hn > 0) hipLaunchKernelGGL(h_normalise, dim3(ew_blocks(G.n)), dim3(256), 0, s, w, G.n, G.sc + slot);
-      // Hessenberg column j of H = gamma I + K: h[0..j] (+ gamma on the diagonal), hn; apply the previous
-      // rotations, then a new one
-      for (int k = 0; k <= j; ++k) H[(size_t)k * restart + j] = h[k];
-      H[(size_t)j * restart + j] += gamma;
-      H[(size_t)(j + 1) * restart + j] = hn;
+      double ss = 0.0, sz = 0.0;
       for (int k = 0; k < j; ++k) {
-        const double a = H[(size_t)k * restart + j], c = H[(size_t)(k + 1) * restart + j];
-        H[(size_t)k * restart + j] = cs[k] * a + sn[k] * c;
-        H[(size_t)(k + 1) * restart + j] = -sn[k] * a + cs[k] * c;
+        ss += sv[k] * sv[k];
+        sz += sv[k] * zv[k];
       }
-      const double a = H[(size_t)j * restart + j], c = H[(size_t)(j + 1) * restart + j];
-      const double d = std::hypot(a, c);
-      cs[j] = d > 0 ? a / d : 1.0;
-      sn[j] = d > 0 ? c / d : 0.0;
-      H[(size_t)j * restart + j] = d;
-      H[(size_t)(j + 1) * restart + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      rel = std::fabs(g[j + 1]) / nb;
-      if (rel <= rtol || hn == 0.0) {
-        ++j;
-        ++it;
-        converged = true;
-        break;
+      // the candidate's norm after its second projection (Pythagoras: s is small against u)
+      const double b2 = j > 0 ? au[0] - ss : 1.0;
+      if (!std::isfinite(b2) || !std::isfinite(au[1])) return set_error(DG_ERR_NONFINITE, "non-finite Arnoldi vector");
+      const double bj = b2 > 0.0 ? std::sqrt(b2) : 0.0;
+      if (j > 0) {
+        // finish column j-1: K v_{j-1} = sum_k (HK[k][j-1] + s_k) v_k + beta_j v_j
+        for (int k = 0; k < j; ++k) HK[k * ld + j - 1] += sv[k];
+        HK[j * ld + j - 1] = bj;
+        // its column of H = gamma I + K, rotated
+        const int c = j - 1;
+        for (int k = 0; k <= j; ++k) R[k * ld + c] = HK[k * ld + c];
+        R[c * ld + c] += gamma;
+        for (int k = 0; k < c; ++k) {
+          const double a = R[k * ld + c], d = R[(k + 1) * ld + c];
+          R[k * ld + c] = cs[k] * a + sn[k] * d;
+          R[(k + 1) * ld + c] = -sn[k] * a + cs[k] * d;
+        }
+        const double a = R[c * ld + c], d = R[(c + 1) * ld + c];
+        const double hyp = std::hypot(a, d);
+        cs[c] = hyp > 0 ? a / hyp : 1.0;
+        sn[c] = hyp > 0 ? d / hyp : 0.0;
+        R[c * ld + c] = hyp;
+        R[(c + 1) * ld + c] = 0.0;
+        g[c + 1] = -sn[c] * g[c];
+        g[c] = cs[c] * g[c];
+        rel = std::fabs(g[c + 1]) / nb;
+        dim = j;
+        if (rel <= rtol || bj == 0.0) {
+          converged = true;
+          break;
+        }
       }
+      if (!more) break;
+      // column j: with v_j = (u_j - V s) / beta_j, K v_j = (w - K V s) / beta_j and K V s = V_{j+1} HK s, so
+      // HK[k][j] = v_k . K v_j = (z_k - (HK s)_k) / beta_j (k < j), HK[j][j] = (gj - (HK s)_j) / beta_j with
+      // gj = v_j . w = (u.w - s.z) / beta_j, and u_{j+1} = (w - V z) / beta_j - (gj / beta_j) v_j
+      const double gj = (au[1] - sz) / bj;
+      for (int k = 0; k <= j; ++k) {
+        double t = 0.0;
+        for (int l = 0; l < j; ++l) t += HK[k * ld + l] * sv[l];
+        y[k] = t;
+      }
+      for (int k = 0; k < j; ++k) HK[k * ld + j] = (zv[k] - y[k]) / bj;
+      HK[j * ld + j] = (gj - y[j]) / bj;
+      if ((rc = G.dupdate(j, true, 1.0 / bj, gj / bj))) return rc;
+      ++it;
     }
-    // x += V y with R y = g (back substitution on the rotated Hessenberg)
-    const int kk = j;
+    // x += V y with R y = g (back substitution on the rotated Hessenberg matrix)
+    const int kk = dim;
     Coef cf{};
     for (int i = kk - 1; i >= 0; --i) {
       double t = g[i];
-      for (int k = i + 1; k < kk; ++k) t -= H[(size_t)i * restart + k] * cf.y[k];
-      cf.y[i] = t / H[(size_t)i * restart + i];
+      for (int k = i + 1; k < kk; ++k) t -= R[(size_t)i * ld + k] * cf.y[k];
+      cf.y[i] = t / R[(size_t)i * ld + i];
     }
     hipLaunchKernelGGL(h_update, dim3(ew_blocks(G.n)), dim3(256), 0, s, x, G.V, G.stride, G.n, kk, cf);
     if ((rc = check_hip(hipGetLastError(), "helmholtz update"))) return rc;
@@ -425,7 +481,6 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
   }
   stats.iterations = it;
   stats.restarts = restarts;
-  stats.reorthogonalised = reorth;
   stats.rel_resid = rel;
   stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (st) *st = stats;
