@@ -26,9 +26,12 @@ namespace dgwm {
 
 namespace {
 
-// Safeguarded Newton for Spalding's law.  f(U) is increasing and convex on
-// U >= 0 with f(0) = -y+ <= 0 <= f(y+), so [0, y+] brackets the root; steps
-// leaving the bracket fall back to bisection.
+// Safeguarded Halley iteration for Spalding's law.  f(U) is increasing and
+// convex on U >= 0 with f(0) = -y+ <= 0 <= f(y+), so [0, y+] brackets the
+// root; the cubic step x - f f' / (f'^2 - f f''/2) (f'' = c kappa^2 (e^k - 1
+// - k) costs nothing beyond the exponential already formed) falls back to
+// Newton where its denominator is not positive and to bisection where a step
+// leaves the bracket.
 __device__ void spalding_root(double yp, double kappa, double B, double& U, double& dU) {
   const double c = exp(-kappa * B);
   double lo = 0.0, hi = yp;
@@ -40,7 +43,9 @@ __device__ void spalding_root(double yp, double kappa, double B, double& U, doub
     if (f == 0.0) break;
     if (f > 0.0) hi = x; else lo = x;
     const double df = 1.0 + c * kappa * (em1 - k - 0.5 * k * k);
-    double xn = x - f / df;
+    const double d2f = c * kappa * kappa * (em1 - k);
+    const double den = df * df - 0.5 * f * d2f;
+    double xn = den > 0.0 ? x - f * df / den : x - f / df;
     if (!(xn >= lo && xn <= hi)) xn = 0.5 * (lo + hi);
     const double step = fabs(xn - x);
     x = xn;
