@@ -905,7 +905,8 @@ static double eval_p(const ctx *C, const double *p, int64_t e, const double xi[3
 }
 
 /* Pressure gradient term for every velocity test function v of cell e
- * (N_B e_c and, in an enriched cell, psi e_c):
+ * (N_B e_c and, in an enriched cell, the enrichment functions psi N^l_B e_c
+ * of Sec. 3.1 eq. enrichment: psi e_c for l = 0):
  *   g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e},  {{p}} = (p- + p+)/2,
  * with the external value p+ = p- on no-slip walls (the pressure's
  * homogeneous Neumann condition) and the velocity quadrature of the cell and
@@ -913,8 +914,10 @@ static double eval_p(const ctx *C, const double *p, int64_t e, const double xi[3
 static void grad_cell(const ctx *C, const double *p, int64_t e, double *g, double *bv, double (*bg)[3],
                       double *pv, double (*pg)[3]) {
   int n = C->npu, np3 = n * n * n;
+  const int nle = C->nle;
   double *ge = g + (int64_t)e * 3 * np3;
-  double gt[3] = {0, 0, 0};
+  double gt[24] = {0};  /* [c][B] */
+  double ev[8], eg[8][3];
   for (int i = 0; i < 3 * np3; ++i) ge[i] = 0.0;
   int enriched = C->enr[e] >= 0;
   const double *q[3], *w[3];
@@ -934,7 +937,10 @@ static void grad_cell(const ctx *C, const double *p, int64_t e, double *g, doubl
         if (enriched) {
           psi_pt ps;
           eval_psi(C, e, xi, Ji, &ps);
-          for (int c = 0; c < 3; ++c) gt[c] -= wq * ps.g[c] * ph;
+          enr_basis(C, xi, Ji, &ps, ev, eg);
+          /* div (psi N_B e_c) = d_c (psi N_B) */
+          for (int c = 0; c < 3; ++c)
+            for (int B = 0; B < nle; ++B) gt[c * nle + B] -= wq * eg[B][c] * ph;
         }
       }
   for (int f = 0; f < 6; ++f) {
@@ -965,13 +971,15 @@ static void grad_cell(const ctx *C, const double *p, int64_t e, double *g, doubl
         if (enriched) {
           psi_pt ps;
           eval_psi(C, e, xi, Ji, &ps);
-          for (int c = 0; c < 3; ++c) gt[c] += wf * ps.psi * nv[c] * pavg;
+          enr_basis(C, xi, Ji, &ps, ev, eg);
+          for (int c = 0; c < 3; ++c)
+            for (int B = 0; B < nle; ++B) gt[c * nle + B] += wf * ev[B] * nv[c] * pavg;
         }
       }
   }
   if (enriched) {
-    double *go = g + C->ncell * 3 * np3 + C->enr[e] * 3;
-    for (int c = 0; c < 3; ++c) go[c] = gt[c];
+    double *go = g + C->ncell * 3 * np3 + C->enr[e] * 3 * nle;
+    for (int i = 0; i < 3 * nle; ++i) go[i] = gt[i];
   }
 }
 
@@ -1035,7 +1043,7 @@ static void div_cell(const ctx *C, const double *u, int64_t e, double *out, doub
 static int mixed_op(const orc_params *P, const double *in, const double *tau_w, const double *tau_nodes,
                     const int64_t *cells, int64_t ncells, double *out, int divergence) {
   ctx C;
-  if (ctx_init_l0(&C, P, tau_w)) return -1;
+  if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
@@ -1083,7 +1091,7 @@ int orc_velocity_divergence(const orc_params *P, const double *u, const double *
 int orc_divdiv_tau(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
                    double dt_over_cr, const int64_t *cells, int64_t ncells, double *tau_d) {
   ctx C;
-  if (ctx_init_l0(&C, P, tau_w)) return -1;
+  if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
@@ -1122,17 +1130,18 @@ int orc_divdiv_tau(const orc_params *P, const double *u, const double *tau_w, co
 }
 
 /* Div-div penalty D(v, u) = (div v, tau_D div u)_e for every velocity test
- * function v of the listed cells (N_B e_c, and psi e_c in enriched cells),
+ * function v of the listed cells (N_B e_c, and psi N^l_B e_c in enriched cells),
  * u the full velocity, tau_D per cell, the cell's velocity rule.  Out:
  * velocity layout. */
 int orc_divdiv_apply(const orc_params *P, const double *u, const double *tau_w, const double *tau_nodes,
                      const double *tau_d, const int64_t *cells, int64_t ncells, double *out) {
   ctx C;
-  if (ctx_init_l0(&C, P, tau_w)) return -1;
+  if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);
   int n = C.npu, np3 = n * n * n;
+  const int nle = C.nle;
   int err = 0;
 #pragma omp parallel
   {
@@ -1142,7 +1151,7 @@ int orc_divdiv_apply(const orc_params *P, const double *u, const double *tau_w, 
     for (int64_t i = 0; i < ncells; ++i) {
       int64_t e = cells[i];
       if (e < 0 || e >= C.ncell) { err = -3; continue; }
-      double *oe = out + e * 3 * np3, ot[3] = {0, 0, 0};
+      double *oe = out + e * 3 * np3, ot[24] = {0};
       for (int k = 0; k < 3 * np3; ++k) oe[k] = 0.0;
       const double *q[3], *w[3];
       int nq[3];
@@ -1156,15 +1165,16 @@ int orc_divdiv_apply(const orc_params *P, const double *u, const double *tau_w, 
             vel_pt vp;
             eval_vel(&C, u, e, xi, Ji, 0, &vp, bv, bg);
             double f = wq * tau_d[e] * (vp.g[0][0] + vp.g[1][1] + vp.g[2][2]);
-            /* div (N_B e_c) = d_c N_B;  div (psi e_c) = d_c psi */
+            /* div (N_B e_c) = d_c N_B;  div (psi N^l_B e_c) = d_c (psi N^l_B) */
             for (int c = 0; c < 3; ++c)
               for (int B = 0; B < np3; ++B) oe[c * np3 + B] += bg[B][c] * f;
             if (vp.enriched)
-              for (int c = 0; c < 3; ++c) ot[c] += vp.psi.g[c] * f;
+              for (int c = 0; c < 3; ++c)
+                for (int B = 0; B < nle; ++B) ot[c * nle + B] += vp.eg[B][c] * f;
           }
       if (C.enr[e] >= 0) {
-        double *oo = out + C.ncell * 3 * np3 + C.enr[e] * 3;
-        for (int c = 0; c < 3; ++c) oo[c] = ot[c];
+        double *oo = out + C.ncell * 3 * np3 + C.enr[e] * 3 * nle;
+        for (int k = 0; k < 3 * nle; ++k) oo[k] = ot[k];
       }
     }
     free(bv);

@@ -123,9 +123,7 @@ def test_l0_only_operators_refuse_l1():
     u = np.zeros(cfg.n_vel)
     tau = np.ones(cfg.n_tau)
     with pytest.raises(RuntimeError):
-        O.velocity_divergence(cfg, u, tau)
-    with pytest.raises(RuntimeError):
-        O.divdiv_tau(cfg, u, 0.1, tau)
+        O.wall_shear_nodes(cfg, u, tau)
     with pytest.raises(NotImplementedError):
         OP.project(cfg, u, np.ones((cfg.n_enriched, 1)), np.ones((cfg.n_enriched, 1)))
     with pytest.raises(NotImplementedError):
@@ -173,3 +171,100 @@ def test_l1_helmholtz_oracle_solves_its_equation():
     psi = O.psi_volume(cfg, O.enriched_cells(cfg), tau=inp["tau"])
     assert np.abs(r).max() <= 1e-9 * 30.0 * np.abs(OP.mass_apply(cfg, b, psi)).max()
     assert its > 0
+
+
+@pytest.mark.parametrize("name", list(CASES_POU))
+def test_divgrad_divdiv_partition_of_unity(name):
+    """P, C, tau_D and D (Sec. 4.2, eqs. div-div, tauD): eight equal vertex
+    coefficients give the l = 0 divergence, tau_D and div-div rows, and the
+    eight enrichment rows of a component (P, D) sum to its l = 0 row."""
+    wl = CASES_POU[name]
+    cfg0 = wl.mesh
+    cfg1 = cfg0.with_(enrich_degree=1)
+    inp = draw_inputs(wl)
+    tau = inp["tau"]
+    n = cfg0.ncell * 3 * (cfg0.k_u + 1) ** 3
+    u0 = inp["u"]
+    u1 = _rep8(cfg0, u0)
+    p = np.random.default_rng(73).uniform(-1, 1, cfg0.n_p)
+    c0, c1 = O.velocity_divergence(cfg0, u0, tau=tau), O.velocity_divergence(cfg1, u1, tau=tau)
+    assert np.abs(c1 - c0).max() <= 1e-13 * np.abs(c0).max()
+    t0, t1 = O.divdiv_tau(cfg0, u0, 0.1, tau=tau), O.divdiv_tau(cfg1, u1, 0.1, tau=tau)
+    assert np.abs(t1 - t0).max() <= 1e-13 * np.abs(t0).max()
+    for f0, f1 in ((O.pressure_gradient(cfg0, p, tau=tau), O.pressure_gradient(cfg1, p, tau=tau)),
+                   (O.divdiv_apply(cfg0, u0, t0, tau=tau), O.divdiv_apply(cfg1, u1, t0, tau=tau))):
+        scale = np.abs(f0).max()
+        assert np.abs(f1[:n] - f0[:n]).max() <= 1e-13 * scale
+        rows = f1[n:].reshape(-1, 3, 8)
+        assert np.abs(rows.sum(axis=2) - f0[n:].reshape(-1, 3)).max() <= 1e-13 * scale
+        assert np.abs(rows - rows.mean(axis=2, keepdims=True)).max() > 1e-6 * np.abs(rows).max()
+
+
+def _linear_psi_setup(k, gamma, seed):
+    """Enriched mesh (l = 1, vanishing tau_w: psi = y+ linear in y), the
+    mesh without enrichment, a velocity (ubar, ut) of the first and the
+    polynomial field it equals on the second, and psi N_B at the nodes of
+    every enriched cell."""
+    nq = (3 * k) // 2 + 1
+    base = MeshConfig(nx=2, ny=3, nz=2, gamma=gamma, k_u=k, k_p=k - 1, nq_u=nq, nq_wn=nq, nq_p=k,
+                      enrich_degree=1)
+    tau_val = 1e-14
+    cfg_p = base.with_(enrich_lower=0, enrich_upper=0)
+    n = k + 1
+    n3 = n ** 3
+    rng = np.random.default_rng(seed)
+    ubar = rng.uniform(-1, 1, base.ncell * 3 * n3)
+    s = math.sqrt(tau_val) / base.nu
+    eta = O.vertex_eta(base)
+    ut = rng.uniform(-1, 1, 24 * base.n_enriched) / (2 * s)
+    nodes = O.gauss_lobatto(n)
+    up = ubar.copy().reshape(base.ncell, 3, n3)
+    weights = {}
+    enr = 0
+    for e in range(base.ncell):
+        ey = (e // base.nx) % base.ny
+        if ey not in (0, base.ny - 1):
+            continue
+        pn = np.zeros((8, n3))
+        for m in range(n):
+            for j in range(n):
+                for i in range(n):
+                    y = eta[ey] + (eta[ey + 1] - eta[ey]) * nodes[j]
+                    ps = s * ((y + 1) if ey == 0 else (1 - y))
+                    for b in range(8):
+                        pn[b, i + n * (j + n * m)] = ps * _vertex_fn(b, (nodes[i], nodes[j], nodes[m]))
+        for c in range(3):
+            up[e, c] += ut[24 * enr + 8 * c: 24 * enr + 8 * c + 8] @ pn
+        weights[e] = (enr, pn)
+        enr += 1
+    return base, cfg_p, np.concatenate([ubar, ut]), up.ravel(), weights, np.full(base.n_tau, tau_val)
+
+
+def _check_rows(base, f_e, f_p, weights):
+    """Polynomial rows equal; each enrichment row is the polynomial rows weighted by psi N_B."""
+    n3 = (base.k_u + 1) ** 3
+    nb = base.ncell * 3 * n3
+    scale = np.abs(f_p).max()
+    assert np.abs(f_e[:nb] - f_p).max() < 1e-12 * scale
+    fp = f_p.reshape(base.ncell, 3, n3)
+    ft = f_e[nb:].reshape(-1, 3, 8)
+    for e, (i, pn) in weights.items():
+        exp = fp[e] @ pn.T
+        assert np.abs(ft[i] - exp).max() < 1e-11 * np.abs(exp).max() + 1e-12 * scale * pn.max()
+
+
+@pytest.mark.parametrize("k,gamma", [(2, 0.0), (3, 1.1)])
+def test_divgrad_divdiv_with_linear_psi_reduce_to_polynomial_path(k, gamma):
+    """With psi = y+ every psi N_B is a polynomial of the cell: the l = 1
+    divergence and tau_D of (ubar, ut) equal those of the interpolated
+    polynomial field on the mesh without enrichment, and P and D give the
+    same polynomial rows with enrichment rows weighted by psi N_B at the
+    nodes (both sides of D)."""
+    base, cfg_p, u_e, u_p, weights, tau = _linear_psi_setup(k, gamma, 20 + k)
+    c_e, c_p = O.velocity_divergence(base, u_e, tau=tau), O.velocity_divergence(cfg_p, u_p)
+    assert np.abs(c_e - c_p).max() < 1e-12 * np.abs(c_p).max()
+    t_e, t_p = O.divdiv_tau(base, u_e, 0.2, tau=tau), O.divdiv_tau(cfg_p, u_p, 0.2)
+    assert np.abs(t_e - t_p).max() < 1e-12 * np.abs(t_p).max()
+    p = np.random.default_rng(30 + k).uniform(-1, 1, base.n_p)
+    _check_rows(base, O.pressure_gradient(base, p, tau=tau), O.pressure_gradient(cfg_p, p), weights)
+    _check_rows(base, O.divdiv_apply(base, u_e, t_p, tau=tau), O.divdiv_apply(cfg_p, u_p, t_p), weights)
