@@ -97,8 +97,10 @@ typedef struct {
                           /*   enrichment): 0 or 1.  l = 1 is built for flat walls and, of  */
                           /*   the velocity operators, for dg_apply_velocity_residual,      */
                           /*   dg_apply_convective, dg_eddy_viscosity,                      */
-                          /*   dg_apply_viscous_multiscale, dg_apply_inverse_mass and       */
-                          /*   dg_solve_helmholtz; every other entry point that reads or    */
+                          /*   dg_apply_viscous_multiscale, dg_apply_inverse_mass,          */
+                          /*   dg_solve_helmholtz, dg_apply_pressure_gradient,              */
+                          /*   dg_apply_velocity_divergence, dg_divdiv_tau and              */
+                          /*   dg_apply_divdiv; every other entry point that reads or       */
                           /*   writes a velocity vector (the batched residual included)     */
                           /*   returns DG_ERR_UNSUPPORTED for it                            */
   int32_t omit_step_tables; /* 1: the mesh workspace leaves out the projection-step tables  */
@@ -279,8 +281,9 @@ int dg_apply_inverse_mass(const dg_mesh* mesh, const double* r, double* x, void*
 
 /* Pressure gradient term of the dual-splitting scheme (paper Sec. 4.2):
  *   g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}
- * for every velocity test function v (N_B e_c, and psi e_c in enriched
- * cells), {{p}} the central average of the two traces, on no-slip walls the
+ * for every velocity test function v (N_B e_c, and in enriched cells psi e_c
+ * for l = 0 or psi N_B e_c over the eight vertex functions for l = 1), {{p}}
+ * the central average of the two traces, on no-slip walls the
  * interior value {{p}} = p- (Sec. 4.2, projection step).  Velocity quadrature of the cell (nq_u^3, nq_u x
  * nq_wn x nq_u in enriched cells) and of its faces.  Flat meshes only.
  *   p: device, dg_num_dofs(mesh, 1) doubles; g: device, dg_num_dofs(mesh, 0)
@@ -291,7 +294,8 @@ int dg_apply_pressure_gradient(const dg_mesh* mesh, const double* p, double* g, 
 
 /* Velocity divergence term (paper Sec. 4.2):
  *   c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}
- * for every pressure test function q, u the full velocity (psi u~ included),
+ * for every pressure test function q, u the full velocity (its enrichment
+ * included, for l = 1 the neighbour's four coefficients on a shared face),
  * on no-slip walls the interior value {{u}} = u- (Sec. 4.2, the boundary
  * condition of this term in the pressure Poisson equation); the same
  * quadrature as the gradient, so that q^T C u = -u^T P q wherever the rules
@@ -312,8 +316,9 @@ int dg_apply_velocity_divergence(const dg_mesh* mesh, const double* u, double* c
 int dg_divdiv_tau(const dg_mesh* mesh, const double* u, double dt_over_cr, double* tau_d, void* stream);
 
 /* Div-div penalty (paper Sec. 4.2, eq. div-div): out(v) = (div v, tau_D,e div u)_e
- * for every velocity test function v (N_B e_c, and psi e_c in enriched cells),
- * u the full velocity, with the cell's velocity rule; cell-local.
+ * for every velocity test function v (N_B e_c, and the enrichment functions
+ * psi e_c (l = 0) or psi N_B e_c (l = 1) in enriched cells), u the full
+ * velocity, with the cell's velocity rule; cell-local.
  *   tau_d: device, nx*ny*nz doubles (e.g. from dg_divdiv_tau); u, out:
  *   device, dg_num_dofs(mesh, 0) doubles, distinct.  Flat meshes only.
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */

@@ -442,7 +442,6 @@ int dg_apply_inverse_mass(const dg_mesh* m, const double* r, double* x, void* st
 int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, void* stream) {
   if (!m || !p || !g) return set_error(DG_ERR_ARG, "mesh/p/g is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "pressure gradient: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (static_cast<const void*>(p) == static_cast<const void*>(g)) return set_error(DG_ERR_ARG, "p and g must not alias");
   if (!aligned256(p) || !aligned256(g)) return set_error(DG_ERR_ARG, "p and g must be 256-byte aligned");
   return launch_divgrad(m, false, p, g, static_cast<hipStream_t>(stream));
@@ -451,7 +450,6 @@ int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, voi
 int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, void* stream) {
   if (!m || !u || !c) return set_error(DG_ERR_ARG, "mesh/u/c is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "velocity divergence: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (static_cast<const void*>(u) == static_cast<const void*>(c)) return set_error(DG_ERR_ARG, "u and c must not alias");
   if (!aligned256(u) || !aligned256(c)) return set_error(DG_ERR_ARG, "u and c must be 256-byte aligned");
   return launch_divgrad(m, true, u, c, static_cast<hipStream_t>(stream));
@@ -460,7 +458,6 @@ int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, v
 int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* tau_d, void* stream) {
   if (!m || !u || !tau_d) return set_error(DG_ERR_ARG, "mesh/u/tau_d is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!(dt_over_cr >= 0) || !std::isfinite(dt_over_cr)) return set_error(DG_ERR_ARG, "dt/Cr must be >= 0 and finite");
   if (static_cast<const void*>(u) == static_cast<const void*>(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must not alias");
   if (!aligned256(u) || !aligned256(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must be 256-byte aligned");
@@ -470,7 +467,6 @@ int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* 
 int dg_apply_divdiv(const dg_mesh* m, const double* tau_d, const double* u, double* out, void* stream) {
   if (!m || !tau_d || !u || !out) return set_error(DG_ERR_ARG, "mesh/tau_d/u/out is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (u == out) return set_error(DG_ERR_ARG, "u and out must not alias");
   if (!aligned256(u) || !aligned256(out) || !aligned256(tau_d))
     return set_error(DG_ERR_ARG, "tau_d, u and out must be 256-byte aligned");

@@ -1,8 +1,9 @@
 """GPU operators with degree-1 enrichment weights (Sec. 3.1 eq.
 enrichment, l = 1: psi times the eight trilinear vertex functions, 24
 enrichment unknowns per enriched cell) against the CPU oracle, through the C
-ABI: the velocity residual, and the pieces of the Helmholtz step (eddy
-viscosity, multiscale viscous operator, inverse mass, GMRES solve).
+ABI: the velocity residual, the pieces of the Helmholtz step (eddy
+viscosity, multiscale viscous operator, inverse mass, GMRES solve), and the
+pressure gradient, velocity divergence and div-div terms with tau_D.
 
 FP64: polynomial and enrichment blocks each at 1e-12 of the oracle's largest
 value, as for l = 0.  FP32: elementwise against the oracle's absolute-value
@@ -117,7 +118,7 @@ def test_l1_unsupported_entry_points():
     mesh = Mesh(wl.mesh, draw_inputs(wl)["tau"])
     u = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
     for call in (lambda: mesh.project_velocity(u), lambda: mesh.vorticity(u),
-                 lambda: mesh.apply_velocity_divergence(u)):
+                 lambda: mesh.wall_shear_nodes(u)):
         with pytest.raises(DgError) as ei:
             call()
         assert ei.value.code == -6
@@ -233,3 +234,36 @@ def test_l1_helmholtz_and_iterations_against_l0(name):
         assert st.rel_resid <= 1e-10
         assert np.abs(res).max() <= 1e-8 * scale
     _log(f"[gpu]   iterations l=1 / l=0 = {its[1] / max(its[0], 1):.2f}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_l1_divgrad_divdiv(name):
+    """Pressure gradient P p (enrichment rows psi N_B e_c), velocity divergence
+    C u (the 24 enrichment coefficients on both sides of every face), tau_D
+    and the div-div penalty (Sec. 4.2, eqs. div-div, tauD) with l = 1, at
+    1e-12 of the oracle per block."""
+    wl = CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] l=1 P, C, tau_D, D case={name}")
+    inp = draw_inputs(wl)
+    rng = np.random.default_rng(87)
+    p = rng.uniform(-1, 1, cfg.n_p)
+    mesh = Mesh(cfg, inp["tau"])
+    ut = torch.tensor(inp["u"], device="cuda")
+    g = mesh.apply_pressure_gradient(torch.tensor(p, device="cuda")).cpu().numpy()
+    c = mesh.apply_velocity_divergence(ut).cpu().numpy()
+    td = mesh.divdiv_tau(ut, 0.05)
+    d = mesh.apply_divdiv(td, ut).cpu().numpy()
+    td = td.cpu().numpy()
+    g_o = O.pressure_gradient(cfg, p, tau=inp["tau"])
+    c_o = O.velocity_divergence(cfg, inp["u"], tau=inp["tau"])
+    td_o = O.divdiv_tau(cfg, inp["u"], 0.05, tau=inp["tau"])
+    d_o = O.divdiv_apply(cfg, inp["u"], td_o, tau=inp["tau"])
+    (gp, ge), (gpo, geo) = _split(cfg, g), _split(cfg, g_o)
+    (dp, de), (dpo, deo) = _split(cfg, d), _split(cfg, d_o)
+    sg, sd = np.abs(g_o).max(), np.abs(d_o).max()
+    _log(f"[gpu]   P {np.abs(gp - gpo).max() / sg:.1e}/{np.abs(ge - geo).max() / sg:.1e}  C {_rel(c, c_o):.1e}  "
+         f"tau_D {_rel(td, td_o):.1e}  D {np.abs(dp - dpo).max() / sd:.1e}/{np.abs(de - deo).max() / sd:.1e}")
+    assert np.abs(gp - gpo).max() <= 1e-12 * sg and np.abs(ge - geo).max() <= 1e-12 * sg
+    assert _rel(c, c_o) <= 1e-12 and _rel(td, td_o) <= 1e-12
+    assert np.abs(dp - dpo).max() <= 1e-12 * sd and np.abs(de - deo).max() <= 1e-12 * sd
