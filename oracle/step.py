@@ -61,10 +61,41 @@ def helmholtz_residual(cfg, u_nut, tau, gamma, b, x):
 # Sec. 4.2 eq. ipflux on the walls)
 # ---------------------------------------------------------------------------
 
+def _vertex_grads(pts, h):
+    """Trilinear vertex functions N_B (B = bx + 2 (by + 2 bz)) at reference
+    points and their physical gradients: (npts, 8), (npts, 8, 3)."""
+    pts = np.asarray(pts, dtype=np.float64)
+    N = np.ones((len(pts), 8))
+    dN = np.ones((len(pts), 8, 3))
+    for b in range(8):
+        for d in range(3):
+            on = (b >> d) & 1
+            f = pts[:, d] if on else 1.0 - pts[:, d]
+            N[:, b] *= f
+            for dd in range(3):
+                dN[:, b, dd] *= ((1.0 if on else -1.0) / h[d]) if dd == d else f
+    return N, dN
+
+
+def _enr_weights(pts, h, ut):
+    """The enrichment weights sum_B N^l_B ut[c][B] at the points and their
+    gradients (Sec. 3.1 eq. enrichment): constants for l = 0, trilinear for
+    l = 1.  Returns (npts, 3) and (npts, 3, 3) [q, component, direction]."""
+    ut = np.asarray(ut, dtype=np.float64)
+    nle = ut.size // 3
+    U = ut.reshape(3, nle)
+    if nle == 1:
+        return np.repeat(U.T, len(pts), axis=0), np.zeros((len(pts), 3, 3))
+    N, dN = _vertex_grads(pts, h)
+    return N @ U.T, np.einsum("qbd,cb->qcd", dN, U)
+
+
 def _cell_grads(cfg, u, e, pts, h, psi4_k, ut):
     """Values (npts, 3) and gradients (npts, 3, 3) [q, component, direction]
-    of the velocity-space field u on cell e at reference points, psi u~
-    included when psi4_k (psi and grad psi at the points) is given."""
+    of the velocity-space field u on cell e at reference points, the
+    enrichment psi sum_B N^l_B u~_B included when psi4_k (psi and grad psi at
+    the points) is given (ut: the cell's 3 (l = 0) or 24 (l = 1) coefficients,
+    [c][B])."""
     from .project import basis_at, _basis_grad_at
     n3 = (cfg.k_u + 1) ** 3
     U = np.asarray(u[e * 3 * n3:(e + 1) * 3 * n3], dtype=np.float64).reshape(3, n3)
@@ -73,8 +104,9 @@ def _cell_grads(cfg, u, e, pts, h, psi4_k, ut):
     val = V @ U.T
     grad = np.einsum("qbd,cb->qcd", G, U)
     if psi4_k is not None:
-        val += psi4_k[:, 0:1] * ut[None, :]
-        grad += ut[None, :, None] * psi4_k[:, None, 1:4]
+        L, dL = _enr_weights(pts, h, ut)
+        val += psi4_k[:, 0:1] * L
+        grad += L[:, :, None] * psi4_k[:, None, 1:4] + psi4_k[:, 0, None, None] * dL
     return V, val, grad
 
 
@@ -83,11 +115,12 @@ def _curl(grad):
 
 
 def vorticity_rhs(cfg, u, tau):
-    """b(v) = (v, curl u)_e for every velocity test function (N_B e_c, and
-    psi e_c in an enriched cell whose enrichment is on) with the cell's
-    velocity rule (nq_u^3, or nq_u x nq_wn x nq_u), u = u_bar + psi u~."""
-    require_l0(cfg)
-    from .project import volume_rule
+    """b(v) = (v, curl u)_e for every velocity test function (N_B e_c, and the
+    enrichment functions psi N^l_B e_c of an enriched cell whose enrichment is
+    on) with the cell's velocity rule (nq_u^3, or nq_u x nq_wn x nq_u),
+    u = u_bar + psi sum_B N^l_B u~_B."""
+    from .project import volume_rule, _nle
+    nle = _nle(cfg)
     n3 = (cfg.k_u + 1) ** 3
     u = np.asarray(u, dtype=np.float64)
     b = np.zeros(cfg.n_vel)
@@ -105,19 +138,19 @@ def vorticity_rhs(cfg, u, tau):
         k = enr.get(e)
         pts, wts = (pts_e, wts_e) if k is not None else (pts_r, wts_r)
         p4 = psi4[k] if k is not None else None
-        ut = u[off + 3 * k:off + 3 * k + 3] if k is not None else None
+        ut = u[off + 3 * nle * k:off + 3 * nle * (k + 1)] if k is not None else None
         V, _, grad = _cell_grads(cfg, u, e, pts, h, p4, ut)
         cw = _curl(grad) * (wts * h[0] * h[1] * h[2])[:, None]
         b[e * 3 * n3:(e + 1) * 3 * n3] = (V.T @ cw).T.reshape(-1)
         if k is not None:
-            b[off + 3 * k:off + 3 * k + 3] = p4[:, 0] @ cw
+            phi = p4[:, 0:1] * (_vertex_grads(pts, h)[0] if nle == 8 else np.ones((len(pts), 1)))   # (npts, nle)
+            b[off + 3 * nle * k:off + 3 * nle * (k + 1)] = (phi.T @ cw).T.reshape(-1)              # [c][B]
     return b
 
 
 def vorticity(cfg, u, tau):
     """omega_h = L2 projection of curl u_h onto the enriched velocity space
     (Sec. 4.2, below eq. ipflux): M omega = vorticity_rhs."""
-    require_l0(cfg)
     return inverse_mass(cfg, vorticity_rhs(cfg, u, tau), _psi(cfg, tau))
 
 
@@ -127,9 +160,10 @@ def pressure_neumann(cfg, us, omegas, betas, f, tau):
       h_N = -( sum_i beta_i (div F^c(u_i) + nu curl omega_i) - f ) . n,
     div F^c(u) = div(u (x) u), n the outward normal (-e_y on the lower wall,
     +e_y on the upper one), at the Gauss points of the velocity face rule
-    (nq_u x nq_u) against the pressure basis; u_i = u_bar + psi u~ and
-    omega_i likewise in enriched cells (psi = 0 on the wall, grad psi not)."""
-    require_l0(cfg)
+    (nq_u x nq_u) against the pressure basis; u_i = u_bar + psi sum_B N^l_B u~_B
+    and omega_i likewise in enriched cells (psi = 0 on the wall, grad psi not)."""
+    from .project import _nle
+    nle = _nle(cfg)
     if cfg.fully_periodic:
         return np.zeros(cfg.n_p)
     npu, npp = cfg.k_u + 1, cfg.k_p + 1
@@ -157,8 +191,8 @@ def pressure_neumann(cfg, us, omegas, betas, f, tau):
                 for u, om, beta in zip(us, omegas, betas):
                     u = np.asarray(u, dtype=np.float64)
                     om = np.asarray(om, dtype=np.float64)
-                    ut = u[off + 3 * k:off + 3 * k + 3] if p4 is not None else None
-                    ot = om[off + 3 * k:off + 3 * k + 3] if p4 is not None else None
+                    ut = u[off + 3 * nle * k:off + 3 * nle * (k + 1)] if p4 is not None else None
+                    ot = om[off + 3 * nle * k:off + 3 * nle * (k + 1)] if p4 is not None else None
                     _, val, g = _cell_grads(cfg, u, e, pts, h, p4, ut)
                     _, _, go = _cell_grads(cfg, om, e, pts, h, p4, ot)
                     div = g[:, 0, 0] + g[:, 1, 1] + g[:, 2, 2]

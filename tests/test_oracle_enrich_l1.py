@@ -126,8 +126,6 @@ def test_l0_only_operators_refuse_l1():
         O.wall_shear_nodes(cfg, u, tau)
     with pytest.raises(NotImplementedError):
         OP.project(cfg, u, np.ones((cfg.n_enriched, 1)), np.ones((cfg.n_enriched, 1)))
-    with pytest.raises(NotImplementedError):
-        OS.vorticity_rhs(cfg, u, tau)
 
 
 def _rep8(cfg0, v):
@@ -268,3 +266,42 @@ def test_divgrad_divdiv_with_linear_psi_reduce_to_polynomial_path(k, gamma):
     p = np.random.default_rng(30 + k).uniform(-1, 1, base.n_p)
     _check_rows(base, O.pressure_gradient(base, p, tau=tau), O.pressure_gradient(cfg_p, p), weights)
     _check_rows(base, O.divdiv_apply(base, u_e, t_p, tau=tau), O.divdiv_apply(cfg_p, u_p, t_p), weights)
+
+
+@pytest.mark.parametrize("name", ["tiny_spalding", "k2_vandriest_stretched"])
+def test_vorticity_and_neumann_partition_of_unity(name):
+    """The vorticity right-hand side (Sec. 4.2, below eq. ipflux) and the
+    wall term of the pressure Neumann data (eq. bc_d_pres): eight equal vertex
+    coefficients give the l = 0 results, and the eight enrichment rows of a
+    component of the vorticity sum to its l = 0 row."""
+    wl = CASES_POU[name]
+    cfg0 = wl.mesh
+    cfg1 = cfg0.with_(enrich_degree=1)
+    inp = draw_inputs(wl)
+    tau = inp["tau"]
+    n = cfg0.ncell * 3 * (cfg0.k_u + 1) ** 3
+    u0 = inp["u"]
+    u1 = _rep8(cfg0, u0)
+    b0, b1 = OS.vorticity_rhs(cfg0, u0, tau), OS.vorticity_rhs(cfg1, u1, tau)
+    scale = np.abs(b0).max()
+    assert np.abs(b1[:n] - b0[:n]).max() <= 1e-13 * scale
+    rows = b1[n:].reshape(-1, 3, 8)
+    assert np.abs(rows.sum(axis=2) - b0[n:].reshape(-1, 3)).max() <= 1e-13 * scale
+    om0 = np.random.default_rng(74).uniform(-1, 1, cfg0.n_vel)
+    h0 = OS.pressure_neumann(cfg0, [u0], [om0], [1.0], (0.0, 0.3, 0.0), tau)
+    h1 = OS.pressure_neumann(cfg1, [u1], [_rep8(cfg0, om0)], [1.0], (0.0, 0.3, 0.0), tau)
+    assert np.abs(h1 - h0).max() <= 1e-13 * np.abs(h0).max()
+
+
+@pytest.mark.parametrize("k,gamma", [(2, 0.0), (3, 1.1)])
+def test_vorticity_and_neumann_with_linear_psi_reduce_to_polynomial_path(k, gamma):
+    """With psi = y+ the l = 1 vorticity right-hand side has the polynomial
+    rows of the interpolated field and enrichment rows weighted by psi N_B at
+    the nodes, and the Neumann wall term of (u, omega) equals that of their
+    polynomial equivalents."""
+    base, cfg_p, u_e, u_p, weights, tau = _linear_psi_setup(k, gamma, 40 + k)
+    _check_rows(base, OS.vorticity_rhs(base, u_e, tau), OS.vorticity_rhs(cfg_p, u_p, None), weights)
+    _, _, om_e, om_p, _, _ = _linear_psi_setup(k, gamma, 50 + k)
+    h_e = OS.pressure_neumann(base, [u_e, u_e], [om_e, om_e], [2.0, -1.0], (0.1, 0.4, 0.0), tau)
+    h_p = OS.pressure_neumann(cfg_p, [u_p, u_p], [om_p, om_p], [2.0, -1.0], (0.1, 0.4, 0.0), None)
+    assert np.abs(h_e - h_p).max() < 1e-12 * np.abs(h_p).max()
