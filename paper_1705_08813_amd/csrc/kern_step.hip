@@ -3,7 +3,9 @@
 // the walls), FP64, flat (box) meshes.
 //
 //   vorticity right-hand side  b(v) = (v, curl u)_e  for every velocity test
-//     function (N_B e_c, and psi e_c in enriched cells), u = u_bar + psi u~,
+//     function (N_B e_c, and in enriched cells psi e_c for l = 0 or psi N_B e_c
+//     over the eight trilinear vertex functions for l = 1, Sec. 3.1 eq.
+//     enrichment), u = u_bar + psi sum_B N_B u~_B,
 //     the cell's velocity rule; omega = M^{-1} b is the L2 projection of
 //     curl u onto the enriched velocity space;
 //   wall term  rhs(q) += int_wall q h_N dA,
@@ -22,6 +24,16 @@ namespace {
 
 constexpr int kVortThreads = 256;
 
+// Trilinear vertex function B (B = bx + 2 (by + 2 bz)) at reference point x
+// and its physical gradient (ih: reciprocal cell sizes).
+__device__ __forceinline__ double st_vtx(int B, const double x[3], const double ih[3], double g[3]) {
+  const double a0 = (B & 1) ? x[0] : 1.0 - x[0], a1 = (B & 2) ? x[1] : 1.0 - x[1], a2 = (B & 4) ? x[2] : 1.0 - x[2];
+  g[0] = ((B & 1) ? ih[0] : -ih[0]) * a1 * a2;
+  g[1] = a0 * ((B & 2) ? ih[1] : -ih[1]) * a2;
+  g[2] = a0 * a1 * ((B & 4) ? ih[2] : -ih[2]);
+  return a0 * a1 * a2;
+}
+
 // Cell layout helpers: (ex, ey, ez) of cell e.
 __device__ __forceinline__ void cell_xyz(const MeshDev& M, int e, int& ex, int& ey, int& ez) {
   ex = e % M.nx;
@@ -33,7 +45,7 @@ __device__ __forceinline__ void cell_xyz(const MeshDev& M, int e, int& ex, int& 
 // b(v) = (v, curl u)_e on the cells of one class (ENR: enriched cells with the
 // NQY-point wall-normal rule; else the others, NQY = NQ).  One block per cell;
 // blocks of the other class leave at once.
-template <int NP, int NQ, int NQY, bool ENR>
+template <int NP, int NQ, int NQY, bool ENR, int LE = 1>
 __global__ __launch_bounds__(kVortThreads) void vort_rhs_kernel(const MeshDev M, const double* __restrict__ u,
                                                                 double* __restrict__ b) {
   constexpr int NP3 = NP * NP * NP, NPT = NQ * NQY * NQ;
@@ -41,6 +53,7 @@ __global__ __launch_bounds__(kVortThreads) void vort_rhs_kernel(const MeshDev M,
   __shared__ double sU[3 * NP3];
   __shared__ double sCW[3 * NPT];  // [component][point]: w |J| curl u
   __shared__ double sPsi[ENR ? NPT : 1];
+  __shared__ double sUt[ENR ? 3 * LE : 1];  // the cell's enrichment coefficients [c][B]
   const int e = blockIdx.x;
   int ex, ey, ez;
   cell_xyz(M, e, ex, ey, ez);
@@ -49,11 +62,7 @@ __global__ __launch_bounds__(kVortThreads) void vort_rhs_kernel(const MeshDev M,
   const double hx = M.hx, hy = M.hy[ey], hz = M.hz;
   const double vol = hx * hy * hz;
   for (int t = threadIdx.x; t < 3 * NP3; t += blockDim.x) sU[t] = u[(int64_t)e * 3 * NP3 + t];
-  double ut[3] = {0, 0, 0};
-  if (ENR) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ut[c] = u[M.enr_off + 3 * k + c];
-  }
+  if (ENR && threadIdx.x < 3 * LE) sUt[threadIdx.x] = u[M.enr_off + 3 * LE * k + threadIdx.x];
   __syncthreads();
   const double* tab = M.tab;
   const double* Sx = tab + L.S;
@@ -92,10 +101,26 @@ __global__ __launch_bounds__(kVortThreads) void vort_rhs_kernel(const MeshDev M,
     }
     if (ENR) {
       const double* p4 = M.psi + ((int64_t)k * M.psi_pts + M.psi_off[0] + t) * 4;
+      if (LE == 1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) g[c][d] += ut[c] * p4[1 + d];
+          for (int d = 0; d < 3; ++d) g[c][d] += sUt[c] * p4[1 + d];
+      } else {
+        // grad(psi sum_B N_B ut_B) = sum_B ut_B (N_B grad psi + psi grad N_B)
+        const double x[3] = {tab[L.g + qx], tab[L.gy + qy], tab[L.g + qz]}, ih[3] = {1.0 / hx, 1.0 / hy, 1.0 / hz};
+#pragma unroll
+        for (int B = 0; B < 8; ++B) {
+          double gn[3];
+          const double nb = st_vtx(B, x, ih, gn);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double w = sUt[c * LE + B];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[c][d] += w * (nb * p4[1 + d] + p4[0] * gn[d]);
+          }
+        }
+      }
       sPsi[t] = p4[0];
     }
     const double w = wq[qx] * wy[qy] * wq[qz] * vol;
@@ -120,11 +145,21 @@ __global__ __launch_bounds__(kVortThreads) void vort_rhs_kernel(const MeshDev M,
     }
     b[(int64_t)e * 3 * NP3 + t] = s;
   }
-  if (ENR && threadIdx.x < 3) {
-    const int c = threadIdx.x;
+  if (ENR && threadIdx.x < 3 * LE) {
+    // enrichment rows: sum over the points of psi N_B w |J| curl u (N_B = 1 for l = 0)
+    const int c = threadIdx.x / LE, B = threadIdx.x - c * LE;
     double s = 0;
-    for (int q = 0; q < NPT; ++q) s += sPsi[q] * sCW[c * NPT + q];
-    b[M.enr_off + 3 * k + c] = s;
+    for (int q = 0; q < NPT; ++q) {
+      double nb = 1.0;
+      if (LE == 8) {
+        const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+        const double x[3] = {tab[L.g + qx], tab[L.gy + qy], tab[L.g + qz]}, ih[3] = {1.0, 1.0, 1.0};
+        double gn[3];
+        nb = st_vtx(B, x, ih, gn);
+      }
+      s += sPsi[q] * nb * sCW[c * NPT + q];
+    }
+    b[M.enr_off + 3 * LE * k + threadIdx.x] = s;
   }
 }
 
@@ -141,7 +176,7 @@ struct NeuArgs {
 // Wall term of the pressure equation: one block per wall cell (lower walls
 // first), threads over the face points, then over the wall-layer pressure
 // nodes of the cell (the other pressure basis functions vanish on the wall).
-template <int NP, int NQ>
+template <int NP, int NQ, int LE = 1>
 __global__ __launch_bounds__(64) void neumann_kernel(const MeshDev M, const NeuArgs A, double* __restrict__ rhs) {
   constexpr int NP3 = NP * NP * NP, NF = NQ * NQ;
   constexpr TabLayout L = tab_layout(NP, NQ, NQ);  // (the S, Sd, w, g, nd tables precede the y rule)
@@ -191,16 +226,35 @@ __global__ __launch_bounds__(64) void neumann_kernel(const MeshDev M, const NeuA
         }
       }
       if (p4) {
-        const double* ut = A.u[h] + M.enr_off + 3 * k;
-        const double* ot = A.om[h] + M.enr_off + 3 * k;
+        const double* ut = A.u[h] + M.enr_off + 3 * LE * k;
+        const double* ot = A.om[h] + M.enr_off + 3 * LE * k;
+        if (LE == 1) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          val[c] += ut[c] * p4[0];
+          for (int c = 0; c < 3; ++c) {
+            val[c] += ut[c] * p4[0];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) g[c][d] += ut[c] * p4[1 + d];
+            for (int d = 0; d < 3; ++d) g[c][d] += ut[c] * p4[1 + d];
+          }
+          gox_z += ot[0] * p4[3];
+          goz_x += ot[2] * p4[1];
+        } else {
+          // enrichment psi sum_B N_B ut_B and its gradient sum_B ut_B (N_B grad psi + psi grad N_B) at the wall
+          // point (psi vanishes there, its gradient does not)
+          const double x[3] = {tab[L.g + qx], wall ? 1.0 : 0.0, tab[L.g + qz]}, ih[3] = {1.0 / hx, 1.0 / hy, 1.0 / hz};
+#pragma unroll
+          for (int B = 0; B < 8; ++B) {
+            double gn[3];
+            const double nb = st_vtx(B, x, ih, gn);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              val[c] += ut[c * LE + B] * nb * p4[0];
+#pragma unroll
+              for (int d = 0; d < 3; ++d) g[c][d] += ut[c * LE + B] * (nb * p4[1 + d] + p4[0] * gn[d]);
+            }
+            gox_z += ot[0 * LE + B] * (nb * p4[3] + p4[0] * gn[2]);
+            goz_x += ot[2 * LE + B] * (nb * p4[1] + p4[0] * gn[0]);
+          }
         }
-        gox_z += ot[0] * p4[3];
-        goz_x += ot[2] * p4[1];
       }
       const double div = g[0][0] + g[1][1] + g[2][2];
       const double conv_y = g[1][0] * val[0] + g[1][1] * val[1] + g[1][2] * val[2] + val[1] * div;
@@ -273,7 +327,9 @@ int launch_vorticity_rhs(const dg_mesh* m, const double* u, double* b, hipStream
   if (!done && np == a && nq == q && (nqw == w || m->nenr == 0)) {                                       \
     done = true;                                                                                         \
     hipLaunchKernelGGL((vort_rhs_kernel<a, q, q, false>), dim3(g), dim3(kVortThreads), 0, s, M, u, b);  \
-    if (m->nenr > 0)                                                                                     \
+    if (m->nenr > 0 && m->nle == 8)                                                                      \
+      hipLaunchKernelGGL((vort_rhs_kernel<a, q, w, true, 8>), dim3(g), dim3(kVortThreads), 0, s, M, u, b); \
+    else if (m->nenr > 0)                                                                                \
       hipLaunchKernelGGL((vort_rhs_kernel<a, q, w, true>), dim3(g), dim3(kVortThreads), 0, s, M, u, b); \
   }
   DG_STEP_COMBOS(X)
@@ -302,7 +358,10 @@ int launch_pressure_neumann(const dg_mesh* m, int nh, const double* const* us, c
 #define X(a, q, w)                                                                                  \
   if (!done && np == a && nq == q) {                                                                \
     done = true;                                                                                    \
-    hipLaunchKernelGGL((neumann_kernel<a, q>), dim3(g), dim3(64), 0, s, M, A, rhs);                 \
+    if (m->nle == 8)                                                                                \
+      hipLaunchKernelGGL((neumann_kernel<a, q, 8>), dim3(g), dim3(64), 0, s, M, A, rhs);            \
+    else                                                                                            \
+      hipLaunchKernelGGL((neumann_kernel<a, q>), dim3(g), dim3(64), 0, s, M, A, rhs);               \
   }
   DG_STEP_COMBOS(X)
 #undef X
@@ -320,7 +379,6 @@ int dg_vorticity_rhs(const dg_mesh* m, const double* u, double* b, void* stream)
   if (!m || !u || !b) return set_error(DG_ERR_ARG, "mesh/u/b is NULL");
   if (u == b) return set_error(DG_ERR_ARG, "u and b must not alias");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the vorticity is built for flat walls only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   return launch_vorticity_rhs(m, u, b, static_cast<hipStream_t>(stream));
 }
 
@@ -328,7 +386,6 @@ int dg_vorticity(const dg_mesh* m, const double* u, double* omega, void* stream)
   if (!m || !u || !omega) return set_error(DG_ERR_ARG, "mesh/u/omega is NULL");
   if (u == omega) return set_error(DG_ERR_ARG, "u and omega must not alias");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the vorticity is built for flat walls only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   const hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = launch_vorticity_rhs(m, u, omega, s);
   if (!rc) rc = launch_inverse_mass(m, omega, omega, s);
@@ -342,7 +399,6 @@ int dg_pressure_neumann(const dg_mesh* m, int32_t nhist, const double* const* u,
   for (int h = 0; h < nhist; ++h)
     if (!u[h] || !omega[h]) return set_error(DG_ERR_ARG, "a velocity or vorticity vector is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Neumann data is built for flat walls only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   return launch_pressure_neumann(m, nhist, u, omega, beta, f, rhs, static_cast<hipStream_t>(stream));
 }
 

@@ -117,8 +117,7 @@ def test_l1_unsupported_entry_points():
     wl = CASES["tiny"]
     mesh = Mesh(wl.mesh, draw_inputs(wl)["tau"])
     u = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
-    for call in (lambda: mesh.project_velocity(u), lambda: mesh.vorticity(u),
-                 lambda: mesh.wall_shear_nodes(u)):
+    for call in (lambda: mesh.project_velocity(u), lambda: mesh.wall_shear_nodes(u)):
         with pytest.raises(DgError) as ei:
             call()
         assert ei.value.code == -6
@@ -267,3 +266,37 @@ def test_l1_divgrad_divdiv(name):
     assert np.abs(gp - gpo).max() <= 1e-12 * sg and np.abs(ge - geo).max() <= 1e-12 * sg
     assert _rel(c, c_o) <= 1e-12 and _rel(td, td_o) <= 1e-12
     assert np.abs(dp - dpo).max() <= 1e-12 * sd and np.abs(de - deo).max() <= 1e-12 * sd
+
+
+@pytest.mark.parametrize("name", ["tiny", "k2_stretched", "k4_large_like", "k3_vandriest_lower", "k3_switch_off"])
+def test_l1_vorticity_and_neumann(name):
+    """The vorticity right-hand side (enrichment rows psi N_B curl u) at 1e-12
+    per block, the projected vorticity by its backward error under the
+    oracle's l = 1 mass matrix, and the wall term of the pressure Neumann data
+    (eq. bc_d_pres) from the GPU vorticities at 1e-12, with l = 1."""
+    wl = CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] l=1 vorticity + Neumann case={name}")
+    inp = draw_inputs(wl)
+    tau = inp["tau"]
+    mesh = Mesh(cfg, tau)
+    rng = np.random.default_rng(88)
+    u1, u2 = inp["u"], rng.uniform(-1, 1, cfg.n_vel)
+    us = [torch.tensor(u1, device="cuda"), torch.tensor(u2, device="cuda")]
+    b = mesh.vorticity_rhs(us[0]).cpu().numpy()
+    ref = OS.vorticity_rhs(cfg, u1, tau)
+    (bp, be), (rp, re) = _split(cfg, b), _split(cfg, ref)
+    sc = np.abs(ref).max()
+    oms = [mesh.vorticity(u) for u in us]
+    om = oms[0].cpu().numpy()
+    psi = O.psi_volume(cfg, O.enriched_cells(cfg), tau=tau)
+    back = OP.mass_apply(cfg, om, psi) - ref
+    bscale = sc + np.abs(OP.mass_apply(cfg, np.abs(om), np.abs(psi))).max()
+    f = (0.3, -0.7, 0.2)
+    rhs = mesh.pressure_neumann(us, oms, (2.0, -1.0), f).cpu().numpy()
+    href = OS.pressure_neumann(cfg, [u1, u2], [o.cpu().numpy() for o in oms], (2.0, -1.0), f, tau)
+    _log(f"[gpu]   rhs poly {np.abs(bp - rp).max() / sc:.1e} enr {np.abs(be - re).max() / sc:.1e}  "
+         f"omega backward {np.abs(back).max() / bscale:.1e}  Neumann {_rel(rhs, href):.1e}")
+    assert np.abs(bp - rp).max() <= 1e-12 * sc and np.abs(be - re).max() <= 1e-12 * sc
+    assert np.abs(back).max() <= 1e-12 * bscale
+    assert _rel(rhs, href) <= 1e-12
