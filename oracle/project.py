@@ -210,6 +210,22 @@ def _nle(cfg):
     return (getattr(cfg, "enrich_degree", 0) + 1) ** 3
 
 
+def _vertex_grads(pts, h):
+    """Trilinear vertex functions N_B (B = bx + 2 (by + 2 bz)) at reference
+    points and their physical gradients (h: cell sizes): (npts, 8), (npts, 8, 3)."""
+    pts = np.asarray(pts, dtype=np.float64)
+    N = np.ones((len(pts), 8))
+    dN = np.ones((len(pts), 8, 3))
+    for b in range(8):
+        for d in range(3):
+            on = (b >> d) & 1
+            f = pts[:, d] if on else 1.0 - pts[:, d]
+            N[:, b] *= f
+            for dd in range(3):
+                dN[:, b, dd] *= ((1.0 if on else -1.0) / h[d]) if dd == d else f
+    return N, dN
+
+
 def _vertex_fns(pts):
     """Trilinear vertex functions N_B (B = bx + 2 (by + 2 bz)) at reference points: (npts, 8)."""
     N = np.ones((len(pts), 8))
@@ -266,7 +282,8 @@ def _basis_grad_at(cfg, pts, h):
 
 def _projection_block(cfg, e, psi4_k, tau_d_e, eta, rule_e, rule_r):
     """M_e and D_e of eq. projectionspat over the local basis of cell e (the
-    three components of N_B, plus psi e_c while the enrichment is on)."""
+    three components of N_B, plus the enrichment functions psi N^l_B e_c
+    while the enrichment is on: psi e_c for l = 0)."""
     n3 = (cfg.k_u + 1) ** 3
     hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
     ey = (e // cfg.nx) % cfg.ny
@@ -276,7 +293,13 @@ def _projection_block(cfg, e, psi4_k, tau_d_e, eta, rule_e, rule_r):
     G = _basis_grad_at(cfg, pts, h)
     w = wts * detJ
     on = psi4_k is not None and bool(np.any(psi4_k[:, 0] != 0.0))
-    nb = 3 * n3 + (3 if on else 0)
+    nle = _nle(cfg)
+    nb = 3 * n3 + (3 * nle if on else 0)
+    if on:
+        # enrichment functions and their gradients: psi N_B, N_B grad psi + psi grad N_B
+        N, dN = _vertex_grads(pts, h) if nle == 8 else (np.ones((len(pts), 1)), np.zeros((len(pts), 1, 3)))
+        phi = psi4_k[:, 0:1] * N
+        gphi = N[:, :, None] * psi4_k[:, None, 1:4] + psi4_k[:, 0, None, None] * dN
     # values (npts, 3, nb) and divergences (npts, nb) of the local basis
     val = np.zeros((len(pts), 3, nb))
     div = np.zeros((len(pts), nb))
@@ -284,20 +307,19 @@ def _projection_block(cfg, e, psi4_k, tau_d_e, eta, rule_e, rule_r):
         val[:, c, c * n3:(c + 1) * n3] = V
         div[:, c * n3:(c + 1) * n3] = G[:, :, c]
         if on:
-            val[:, c, 3 * n3 + c] = psi4_k[:, 0]
-            div[:, 3 * n3 + c] = psi4_k[:, 1 + c]
+            val[:, c, 3 * n3 + c * nle:3 * n3 + (c + 1) * nle] = phi
+            div[:, 3 * n3 + c * nle:3 * n3 + (c + 1) * nle] = gphi[:, :, c]
     M = np.einsum("q,qci,qcj->ij", w, val, val)
     D = tau_d_e * np.einsum("q,qi,qj->ij", w, div, div)
     return M, D, on
 
 
 def projection_block(cfg, e, tau_d_e, psi4_k=None):
-    """(M_e, D_e) of the projection step for cell e: 3 n (+3 while an enriched
-    cell's enrichment is on) square, unknowns ordered as in the velocity
-    layout (components of N_B, then the three enrichment coefficients).
-    psi4_k: psi and grad psi at the enriched volume rule, None for a cell
-    without enrichment."""
-    require_l0(cfg)
+    """(M_e, D_e) of the projection step for cell e: 3 n (+3 (l+1)^3 while an
+    enriched cell's enrichment is on) square, unknowns ordered as in the
+    velocity layout (components of N_B, then the enrichment coefficients
+    [c][B]).  psi4_k: psi and grad psi at the enriched volume rule, None for a
+    cell without enrichment."""
     pts_e, wts_e = volume_rule(cfg)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     M, D, _ = _projection_block(cfg, int(e), psi4_k, tau_d_e, vertex_eta(cfg),
@@ -315,8 +337,8 @@ def projection_step(cfg, u_hat, g, scale, tau_d, psi4, cells=None):
     rule) is assembled from 3-D basis values and gradients and the system is
     solved densely.  psi4: [nenr][npts][4] psi and grad psi at the enriched
     volume rule.  cells: optional subset of cells to solve (others stay 0).
-    Flat (box) meshes only."""
-    require_l0(cfg)
+    With l = 1 the enrichment functions are psi N_B e_c (Sec. 3.1 eq.
+    enrichment).  Flat (box) meshes only."""
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -329,16 +351,17 @@ def projection_step(cfg, u_hat, g, scale, tau_d, psi4, cells=None):
     pts_e, wts_e = volume_rule(cfg)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     V_e, V_r = basis_at(cfg, pts_e), basis_at(cfg, pts_r)
+    ne = 3 * _nle(cfg)
     for e in (range(cfg.ncell) if cells is None else (int(c) for c in cells)):
         k = enr.get(e)
         M, D, on = _projection_block(cfg, e, None if k is None else psi4[k], tau_d[e], eta,
                                      (pts_e, wts_e, V_e), (pts_r, wts_r, V_r))
         # right-hand side: M u_hat - scale g
-        coef = np.concatenate([u_hat[e * 3 * n3:(e + 1) * 3 * n3]] + ([u_hat[off + 3 * k: off + 3 * k + 3]] if on else []))
+        coef = np.concatenate([u_hat[e * 3 * n3:(e + 1) * 3 * n3]] + ([u_hat[off + ne * k: off + ne * (k + 1)]] if on else []))
         rhs = M @ coef - scale * np.concatenate([g[e * 3 * n3:(e + 1) * 3 * n3]] +
-                                                ([g[off + 3 * k: off + 3 * k + 3]] if on else []))
+                                                ([g[off + ne * k: off + ne * (k + 1)]] if on else []))
         sol = np.linalg.solve(M + D, rhs)
         x[e * 3 * n3:(e + 1) * 3 * n3] = sol[:3 * n3]
         if k is not None:
-            x[off + 3 * k: off + 3 * k + 3] = sol[3 * n3:] if on else 0.0
+            x[off + ne * k: off + ne * (k + 1)] = sol[3 * n3:] if on else 0.0
     return x

@@ -13,7 +13,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import (enriched_cells, enrichment_active, gauss, gauss_lobatto, lagrange, psi_point, psi_volume, psi_volume4,
-               require_l0, vertex_eta, viscous_multiscale)
+               vertex_eta, viscous_multiscale)
 from .project import inverse_mass, mass_apply
 
 
@@ -61,22 +61,6 @@ def helmholtz_residual(cfg, u_nut, tau, gamma, b, x):
 # Sec. 4.2 eq. ipflux on the walls)
 # ---------------------------------------------------------------------------
 
-def _vertex_grads(pts, h):
-    """Trilinear vertex functions N_B (B = bx + 2 (by + 2 bz)) at reference
-    points and their physical gradients: (npts, 8), (npts, 8, 3)."""
-    pts = np.asarray(pts, dtype=np.float64)
-    N = np.ones((len(pts), 8))
-    dN = np.ones((len(pts), 8, 3))
-    for b in range(8):
-        for d in range(3):
-            on = (b >> d) & 1
-            f = pts[:, d] if on else 1.0 - pts[:, d]
-            N[:, b] *= f
-            for dd in range(3):
-                dN[:, b, dd] *= ((1.0 if on else -1.0) / h[d]) if dd == d else f
-    return N, dN
-
-
 def _enr_weights(pts, h, ut):
     """The enrichment weights sum_B N^l_B ut[c][B] at the points and their
     gradients (Sec. 3.1 eq. enrichment): constants for l = 0, trilinear for
@@ -86,6 +70,7 @@ def _enr_weights(pts, h, ut):
     U = ut.reshape(3, nle)
     if nle == 1:
         return np.repeat(U.T, len(pts), axis=0), np.zeros((len(pts), 3, 3))
+    from .project import _vertex_grads
     N, dN = _vertex_grads(pts, h)
     return N @ U.T, np.einsum("qbd,cb->qcd", dN, U)
 
@@ -119,7 +104,7 @@ def vorticity_rhs(cfg, u, tau):
     enrichment functions psi N^l_B e_c of an enriched cell whose enrichment is
     on) with the cell's velocity rule (nq_u^3, or nq_u x nq_wn x nq_u),
     u = u_bar + psi sum_B N^l_B u~_B."""
-    from .project import volume_rule, _nle
+    from .project import volume_rule, _nle, _vertex_grads
     nle = _nle(cfg)
     n3 = (cfg.k_u + 1) ** 3
     u = np.asarray(u, dtype=np.float64)
@@ -218,8 +203,8 @@ def dual_splitting_step(cfg, tau, u_n, u_nm1, dt, order=2, f=(0.0, 0.0, 0.0), dt
     least squares, zero mean), projection (eq. projectionspat, tau_D from
     u^n), Helmholtz step (eq. helmholtzspat, nu_t from u^n).  Constant-step
     BDF/extrapolation coefficients of order 1 or 2.  Returns (u^{n+1}, p,
-    u_hat, u_hathat)."""
-    require_l0(cfg)
+    u_hat, u_hathat).  With l = 1 every operator takes the degree-1
+    enrichment weights (Sec. 3.1 eq. enrichment)."""
     from . import convective_residual, divdiv_tau, pressure_gradient, velocity_divergence
     from . import solve as osolve
     from .project import projection_step

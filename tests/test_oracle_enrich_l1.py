@@ -305,3 +305,32 @@ def test_vorticity_and_neumann_with_linear_psi_reduce_to_polynomial_path(k, gamm
     h_e = OS.pressure_neumann(base, [u_e, u_e], [om_e, om_e], [2.0, -1.0], (0.1, 0.4, 0.0), tau)
     h_p = OS.pressure_neumann(cfg_p, [u_p, u_p], [om_p, om_p], [2.0, -1.0], (0.1, 0.4, 0.0), None)
     assert np.abs(h_e - h_p).max() < 1e-12 * np.abs(h_p).max()
+
+
+@pytest.mark.parametrize("name", ["tiny_spalding", "k3_lower_only"])
+def test_projection_step_l1_meets_its_equation(name):
+    """The l = 1 projection step (Sec. 4.2, eq. projectionspat) assembled
+    densely per cell satisfies M x + D x = M u_hat - s g with the separately
+    pinned l = 1 mass matrix (partition of unity, M^{-1} M = I) and div-div
+    penalty (linear-psi reduction), to rounding of the cells' blocks."""
+    wl = CASES_POU[name]
+    cfg = wl.mesh.with_(enrich_degree=1)
+    inp = draw_inputs(wl)
+    tau = inp["tau"]
+    rng = np.random.default_rng(75)
+    u = rng.uniform(-1, 1, cfg.n_vel)
+    u_hat = rng.uniform(-1, 1, cfg.n_vel)
+    g = rng.uniform(-1, 1, cfg.n_vel)
+    s = 0.01
+    tau_d = O.divdiv_tau(cfg, u, 0.05, tau=tau)
+    cells = O.enriched_cells(cfg)
+    psi4 = O.psi_volume4(cfg, cells, tau=tau)
+    psi = psi4[:, :, 0]
+    x = OP.projection_step(cfg, u_hat, g, s, tau_d, psi4)
+    lhs = OP.mass_apply(cfg, x, psi) + O.divdiv_apply(cfg, x, tau_d, tau=tau)
+    rhs = OP.mass_apply(cfg, u_hat, psi) - s * g
+    scale = np.abs(OP.mass_apply(cfg, np.abs(x), np.abs(psi))).max() + np.abs(rhs).max()
+    assert np.abs(lhs - rhs).max() <= 1e-12 * scale
+    # the enrichment rows are not trivially zero
+    n = cfg.ncell * 3 * (cfg.k_u + 1) ** 3
+    assert np.abs(x[n:]).max() > 1e-3 * np.abs(x[:n]).max()
