@@ -99,10 +99,11 @@ typedef struct {
                           /*   dg_apply_convective, dg_eddy_viscosity,                      */
                           /*   dg_apply_viscous_multiscale, dg_apply_inverse_mass,          */
                           /*   dg_solve_helmholtz, dg_apply_pressure_gradient,              */
-                          /*   dg_apply_velocity_divergence, dg_divdiv_tau and              */
-                          /*   dg_apply_divdiv; every other entry point that reads or       */
-                          /*   writes a velocity vector (the batched residual included)     */
-                          /*   returns DG_ERR_UNSUPPORTED for it                            */
+                          /*   dg_apply_velocity_divergence, dg_divdiv_tau, dg_apply_divdiv, */
+                          /*   dg_vorticity_rhs, dg_vorticity, dg_pressure_neumann and      */
+                          /*   dg_dual_splitting_step; dg_wall_shear_nodes,                 */
+                          /*   dg_project_velocity, dg_projection_step and the batched      */
+                          /*   residual return DG_ERR_UNSUPPORTED for it                    */
   int32_t omit_step_tables; /* 1: the mesh workspace leaves out the projection-step tables  */
                           /*   (per-layer spectral factors, enriched-cell couplings), so    */
                           /*   dg_projection_step and dg_dual_splitting_step return         */
@@ -653,6 +654,7 @@ typedef struct {
   dg_solve_stats poisson;
   dg_gmres_stats helmholtz;
   double seconds;        /* host wall time of the step                                           */
+  int32_t projection_its;/* l = 1: GMRES iterations of the projection step (l = 0: 0, solved directly) */
 } dg_step_stats;
 
 /* Device workspace of dg_dual_splitting_step (7 velocity vectors, the
@@ -668,7 +670,11 @@ int64_t dg_step_workspace_bytes(const dg_mesh* mesh, const dg_step_params* sp);
  *       + int_wall q h_N, h_N the high-order Neumann data of eq. bc_d_pres from u^{n-i} and
  *       their projected vorticities; solved by dg_solve_poisson with sp->poisson (p holds the
  *       initial guess on entry, e.g. the previous pressure, and the zero-mean p^{n+1} on exit)
- *   3 projection (eq. projectionspat): (M + D) u^^ = M u^ - dt/gamma0 P p, tau_D from u^n
+ *   3 projection (eq. projectionspat): (M + D) u^^ = M u^ - dt/gamma0 P p, tau_D from u^n;
+ *       solved directly for l = 0 (dg_projection_step) and, for l = 1, as the block-diagonal
+ *       u^^ + M^{-1} D u^^ = u^ - dt/gamma0 M^{-1} P p by the GMRES of step 4 (relative
+ *       residual 1e-12, at most 50000 iterations, sp->helmholtz's restart, from u^; the
+ *       near-singular l = 1 mass blocks make this iteration long)
  *   4 Helmholtz (eq. helmholtzspat): (gamma0/dt) M u + A(nu_t) u = (gamma0/dt) M u^^ by
  *       dg_solve_helmholtz with sp->helmholtz, nu_t from the enrichment of u^n, from u^^
  * The wall shear stress and psi are those of the mesh (a caller refreshes them between

@@ -68,7 +68,8 @@ class StepParams(ctypes.Structure):
 
 
 class StepStats(ctypes.Structure):
-    _fields_ = [("poisson", SolveStats), ("helmholtz", GmresStats), ("seconds", ctypes.c_double)]
+    _fields_ = [("poisson", SolveStats), ("helmholtz", GmresStats), ("seconds", ctypes.c_double),
+                ("projection_its", ctypes.c_int32)]
 
 
 # every symbol include/dgwm.h declares, with its signature

@@ -256,6 +256,8 @@ int launch_pressure_neumann(const dg_mesh* m, int nh, const double* const* us, c
 int64_t helmholtz_workspace_bytes(const dg_mesh* m, int restart);
 int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const double* b, double* x, double rtol,
                     int max_iter, int restart, void* ws, size_t ws_bytes, dg_gmres_stats* st, hipStream_t s);
+int solve_projection_gmres(const dg_mesh* m, const double* tau_d, const double* b, double* x, double rtol,
+                           int max_iter, int restart, void* ws, size_t ws_bytes, dg_gmres_stats* st, hipStream_t s);
 // u_new = L2 projection of u_old from the space of psi_prev onto that of psi
 int launch_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, hipStream_t s);
 // nodal wall shear stress [wall][nz][nx] of the FP64 velocity u (flat walls)

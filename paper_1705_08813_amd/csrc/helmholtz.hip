@@ -255,7 +255,8 @@ size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Gm {
   const dg_mesh* m;
-  const double* nut;
+  const double* nut;     // multiscale viscous operator: nu_t of the enriched points
+  const double* tau_d;   // div-div operator (when not null): tau_D per cell
   hipStream_t s;
   int64_t n;
   int64_t stride;  // doubles between Krylov vectors
@@ -265,9 +266,9 @@ struct Gm {
   double gamma;
 
   double* v(int k) const { return V + k * stride; }
-  // y = K x = M^{-1} A x  (y != x)
+  // y = K x = M^{-1} A x  (y != x), A the multiscale viscous operator or, with tau_d, the div-div penalty
   int apply_k(const double* x, double* y) {
-    int rc = launch_viscous_multiscale(m, nut, x, y, s);
+    int rc = tau_d ? launch_divdiv(m, false, x, tau_d, 0.0, y, s) : launch_viscous_multiscale(m, nut, x, y, s);
     if (!rc) rc = launch_inverse_mass(m, y, y, s);
     return rc;
   }
@@ -324,8 +325,10 @@ int64_t helmholtz_workspace_bytes(const dg_mesh* m, int restart) {
                    up256(sizeof(double) * kHRows * kHMaxParts));
 }
 
-int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const double* b, double* x, double rtol,
-                    int max_iter, int restart, void* ws, size_t ws_bytes, dg_gmres_stats* st, hipStream_t s) {
+// gamma x + M^{-1} A x = gamma b, A the multiscale viscous operator (tau_d null) or the div-div penalty
+static int solve_shifted(const dg_mesh* m, const double* nut, const double* tau_d, double gamma, const double* b,
+                         double* x, double rtol, int max_iter, int restart, void* ws, size_t ws_bytes,
+                         dg_gmres_stats* st, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
   if (restart < 1 || restart > kHMaxRestart)
     return set_error(DG_ERR_ARG, "GMRES restart length outside [1, 100]");
@@ -338,6 +341,7 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
   Gm G;
   G.m = m;
   G.nut = nut;
+  G.tau_d = tau_d;
   G.s = s;
   G.n = m->n_vel;
   G.stride = (int64_t)(up256(sizeof(double) * (size_t)G.n) / sizeof(double));
@@ -370,8 +374,7 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
   while (!converged && it < max_iter) {
     // r = gamma b - H x into V_0, beta = ||r||
     double* r = G.v(0);
-    if ((rc = launch_viscous_multiscale(m, nut, x, r, s))) return rc;
-    if ((rc = launch_inverse_mass(m, r, r, s))) return rc;
+    if ((rc = G.apply_k(x, r))) return rc;
     hipLaunchKernelGGL(h_residual, dim3(ew_blocks(G.n)), dim3(256), 0, s, r, b, x, G.n, gamma);
     if ((rc = G.dot(r, r, 0, 1))) return rc;
     double beta;
@@ -466,8 +469,7 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
     else {
       // confirm with the true residual (a restart cycle follows if it is not met)
       double* r = G.v(0);
-      if ((rc = launch_viscous_multiscale(m, nut, x, r, s))) return rc;
-      if ((rc = launch_inverse_mass(m, r, r, s))) return rc;
+      if ((rc = G.apply_k(x, r))) return rc;
       hipLaunchKernelGGL(h_residual, dim3(ew_blocks(G.n)), dim3(256), 0, s, r, b, x, G.n, gamma);
       if ((rc = G.dot(r, r, 0, 1))) return rc;
       double tr;
@@ -487,6 +489,18 @@ int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const dou
   if ((rc = check_hip(hipStreamSynchronize(s), "helmholtz"))) return rc;
   if (!converged) return set_error(DG_ERR_NOT_CONVERGED, "GMRES iteration cap reached");
   return DG_OK;
+}
+
+int solve_helmholtz(const dg_mesh* m, const double* nut, double gamma, const double* b, double* x, double rtol,
+                    int max_iter, int restart, void* ws, size_t ws_bytes, dg_gmres_stats* st, hipStream_t s) {
+  return solve_shifted(m, nut, nullptr, gamma, b, x, rtol, max_iter, restart, ws, ws_bytes, st, s);
+}
+
+// The projection step (M + D) x = M b' as x + M^{-1} D x = b' (b' = u_hat - s M^{-1} g): block diagonal, one
+// GMRES over all cells (used for degree-1 enrichment weights, whose enriched cells have no direct solve here).
+int solve_projection_gmres(const dg_mesh* m, const double* tau_d, const double* b, double* x, double rtol,
+                           int max_iter, int restart, void* ws, size_t ws_bytes, dg_gmres_stats* st, hipStream_t s) {
+  return solve_shifted(m, nullptr, tau_d, 1.0, b, x, rtol, max_iter, restart, ws, ws_bytes, st, s);
 }
 
 }  // namespace dgwm

@@ -24,6 +24,11 @@ namespace dgwm {
 namespace {
 
 size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+// relative residual and iteration cap of the degree-1 projection step's GMRES (the degree-0 path solves
+// directly): the enriched cells' mass blocks are near-singular for l = 1 (condition numbers near 1e8), which
+// spreads the spectrum of M^{-1} D and makes the iteration long
+constexpr double kProjRtol = 1e-12;
+constexpr int kProjMaxIter = 50000;
 unsigned ew_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
 
 // s = b0 s + b1 t
@@ -111,7 +116,6 @@ int dg_dual_splitting_step(const dg_mesh* m, const dg_step_params* sp, const dou
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the dual-splitting step is built for flat walls only");
   if (m->P.omit_step_tables)
     return set_error(DG_ERR_UNSUPPORTED, "the mesh was set up without projection-step tables (omit_step_tables)");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (sp->order != 1 && sp->order != 2) return set_error(DG_ERR_ARG, "order must be 1 or 2");
   if (sp->order == 2 && !u_nm1) return set_error(DG_ERR_ARG, "order 2 needs u_nm1");
   if (!(sp->dt > 0) || !(sp->gamma0 > 0) || !std::isfinite(sp->dt + sp->gamma0) || !(sp->dt_over_cr >= 0))
@@ -119,6 +123,7 @@ int dg_dual_splitting_step(const dg_mesh* m, const dg_step_params* sp, const dou
   if (u_np1 == u_n || u_np1 == u_nm1) return set_error(DG_ERR_ARG, "u_np1 must not alias u_n or u_nm1");
   if (sp->helmholtz.restart < 1 || sp->helmholtz.restart > 100)
     return set_error(DG_ERR_ARG, "GMRES restart outside [1, 100]");
+  if (st) st->projection_its = 0;
   const StepWs W = step_layout(m, sp, static_cast<char*>(ws));
   if (ws_bytes < W.total) return set_error(DG_ERR_WORKSPACE, "step workspace too small");
   const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -160,7 +165,21 @@ int dg_dual_splitting_step(const dg_mesh* m, const dg_step_params* sp, const dou
   // 3 projection: (M + D) u^^ = M u^ - dt/gamma0 P p, tau_D from u^n
   DG_TRY(launch_divgrad(m, false, p, W.g, s));
   DG_TRY(launch_divdiv(m, true, u_n, nullptr, sp->dt_over_cr, W.tau_d, s));
-  DG_TRY(launch_projection_step(m, W.tau_d, W.uh, W.g, sp->dt / sp->gamma0, W.uhh, s));
+  if (m->nle == 1 || m->nenr == 0) {
+    DG_TRY(launch_projection_step(m, W.tau_d, W.uh, W.g, sp->dt / sp->gamma0, W.uhh, s));
+  } else {
+    // degree-1 enrichment weights: u^^ + M^{-1} D u^^ = u^ - dt/gamma0 M^{-1} P p by the restarted GMRES of
+    // the Helmholtz step (block diagonal, the same workspace), from u^
+    DG_TRY(launch_inverse_mass(m, W.g, W.t, s));
+    DG_TRY(check_hip(hipMemcpyAsync(W.s, W.uh, sizeof(double) * nv, hipMemcpyDeviceToDevice, s), "projection rhs"));
+    hipLaunchKernelGGL(st_combine, dim3(ew_blocks(nv)), dim3(256), 0, s, W.s, W.t, nv, 1.0, -sp->dt / sp->gamma0);
+    DG_TRY(check_hip(hipMemcpyAsync(W.uhh, W.uh, sizeof(double) * nv, hipMemcpyDeviceToDevice, s), "initial guess"));
+    dg_gmres_stats pst{};
+    rc = solve_projection_gmres(m, W.tau_d, W.s, W.uhh, kProjRtol, kProjMaxIter, sp->helmholtz.restart, W.hws,
+                                W.hws_bytes, &pst, s);
+    if (st) st->projection_its = pst.iterations;
+    if (rc) return rc;
+  }
 
   // 4 Helmholtz: nu_t from u^n, initial guess u^^
   if (m->nenr > 0) DG_TRY(launch_eddy_viscosity(m, u_n, sp->c_des, sp->beta_des, W.nut, s));

@@ -2,8 +2,9 @@
 enrichment, l = 1: psi times the eight trilinear vertex functions, 24
 enrichment unknowns per enriched cell) against the CPU oracle, through the C
 ABI: the velocity residual, the pieces of the Helmholtz step (eddy
-viscosity, multiscale viscous operator, inverse mass, GMRES solve), and the
-pressure gradient, velocity divergence and div-div terms with tau_D.
+viscosity, multiscale viscous operator, inverse mass, GMRES solve), the
+pressure gradient, velocity divergence and div-div terms with tau_D, the
+vorticity and the pressure Neumann data, and one assembled time step.
 
 FP64: polynomial and enrichment blocks each at 1e-12 of the oracle's largest
 value, as for l = 0.  FP32: elementwise against the oracle's absolute-value
@@ -117,7 +118,9 @@ def test_l1_unsupported_entry_points():
     wl = CASES["tiny"]
     mesh = Mesh(wl.mesh, draw_inputs(wl)["tau"])
     u = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
-    for call in (lambda: mesh.project_velocity(u), lambda: mesh.wall_shear_nodes(u)):
+    td = torch.zeros(wl.mesh.ncell, dtype=torch.float64, device="cuda")
+    for call in (lambda: mesh.project_velocity(u), lambda: mesh.wall_shear_nodes(u),
+                 lambda: mesh.projection_step(td, u, u, 1e-3)):
         with pytest.raises(DgError) as ei:
             call()
         assert ei.value.code == -6
@@ -300,3 +303,32 @@ def test_l1_vorticity_and_neumann(name):
     assert np.abs(bp - rp).max() <= 1e-12 * sc and np.abs(be - re).max() <= 1e-12 * sc
     assert np.abs(back).max() <= 1e-12 * bscale
     assert _rel(rhs, href) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny", "k3_vandriest_lower", "k3_switch_off"])
+def test_l1_dual_splitting_step_matches_oracle(name):
+    """One dual-splitting step (Sec. 4.1 with the forms of Sec. 4.2) with
+    l = 1 against the oracle's step: every operator takes the degree-1
+    weights, the projection step runs as GMRES on u + M^{-1} D u (relative
+    residual 1e-12; the oracle solves each cell densely), the Poisson and
+    Helmholtz solves to 1e-12; u^{n+1} and the zero-mean p^{n+1} agree to
+    1e-8 of their largest value, as for l = 0."""
+    wl = CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] l=1 dual-splitting step case={name}")
+    inp = draw_inputs(wl)
+    tau = inp["tau"]
+    rng = np.random.default_rng(89)
+    u0 = 0.3 * inp["u"]
+    u1 = 0.3 * rng.uniform(-1, 1, cfg.n_vel)
+    dt, f = 0.005, (0.9, 0.0, -0.2)
+    mesh = Mesh(cfg, tau)
+    sp = mesh.step_params(dt, order=2, f=f, poisson=mesh.solve_params(rtol=1e-12, mixed=False), helmholtz_rtol=1e-12)
+    p = torch.zeros(cfg.n_p, dtype=torch.float64, device="cuda")
+    un, p, st = mesh.dual_splitting_step(sp, torch.tensor(u0, device="cuda"), torch.tensor(u1, device="cuda"), p)
+    ref_u, ref_p, _, _ = OS.dual_splitting_step(cfg, tau, u0, u1, dt, order=2, f=f)
+    eu, ep = _rel(un.cpu().numpy(), ref_u), _rel(p.cpu().numpy(), ref_p)
+    _log(f"[gpu]   projection its={st.projection_its}  poisson its={st.poisson.outer_its}  helmholtz its="
+         f"{st.helmholtz.iterations}  |du|={eu:.1e} |dp|={ep:.1e}")
+    assert st.projection_its > 0
+    assert eu <= 1e-8 and ep <= 1e-8
