@@ -100,8 +100,8 @@ typedef struct {
                           /*   dg_apply_viscous_multiscale, dg_apply_inverse_mass,          */
                           /*   dg_solve_helmholtz, dg_apply_pressure_gradient,              */
                           /*   dg_apply_velocity_divergence, dg_divdiv_tau, dg_apply_divdiv, */
-                          /*   dg_vorticity_rhs, dg_vorticity, dg_pressure_neumann and      */
-                          /*   dg_dual_splitting_step; dg_wall_shear_nodes,                 */
+                          /*   dg_vorticity_rhs, dg_vorticity, dg_pressure_neumann,         */
+                          /*   dg_wall_shear_nodes and dg_dual_splitting_step;              */
                           /*   dg_project_velocity, dg_projection_step and the batched      */
                           /*   residual return DG_ERR_UNSUPPORTED for it                    */
   int32_t omit_step_tables; /* 1: the mesh workspace leaves out the projection-step tables  */

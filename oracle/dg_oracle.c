@@ -1440,7 +1440,7 @@ int orc_wall_shear_nodes(const orc_params *P, const double *u, const double *tau
                          double *out) {
   ctx C;
   if (P->fully_periodic || P->wall_amp != 0.0) return -3;
-  if (ctx_init_l0(&C, P, tau_w)) return -1;
+  if (ctx_init(&C, P, tau_w)) return -1;
   C.tau_nodes = tau_nodes;
   if (C.nenr > 0 && !tau_w && !tau_nodes) { ctx_free(&C); return -2; }
   ctx_activity(&C, -1);

@@ -403,7 +403,6 @@ int dg_wall_shear_nodes(const dg_mesh* m, const double* u, double* tau_nodes, vo
   if (!m || !u || !tau_nodes) return set_error(DG_ERR_ARG, "mesh/u/tau_nodes is NULL");
   if (m->curved || m->P.fully_periodic)
     return set_error(DG_ERR_UNSUPPORTED, "nodal wall shear stress: flat no-slip walls only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (static_cast<const void*>(u) == static_cast<const void*>(tau_nodes))
     return set_error(DG_ERR_ARG, "u and tau_nodes must not alias");
   if (!aligned256(u) || !aligned256(tau_nodes)) return set_error(DG_ERR_ARG, "u and tau_nodes must be 256-byte aligned");

@@ -5,7 +5,7 @@
 // N_B is the bilinear hat function of wall vertex B on the periodic
 // (x, z) vertex grid of a wall, n the outward unit normal (-e_y on the lower
 // wall, +e_y on the upper one) and u_h the full velocity, including psi u~ in
-// enriched cells.  On a flat wall (grad u) n = -+ du/dy, so only the
+// enriched cells (psi sum_B N_B u~_B with l = 1).  On a flat wall (grad u) n = -+ du/dy, so only the
 // wall-normal derivative at the wall-face Gauss points of the velocity rule
 // is needed:
 //   du_c/dy = (1/h_y) sum_B N_B'(wall) u_cB + u~_c dpsi/dy,
@@ -31,7 +31,7 @@ constexpr int kWsThreads = 128;
 // blockIdx.x = ex + nx (ez + nz w): the wall cell; part has 12 doubles per block.
 __global__ __launch_bounds__(kWsThreads) void wall_shear_cells(
     int nx, int ny, int nz, int np, int nq, int nq_wn, const double* __restrict__ tab, const double* __restrict__ hy,
-    double hx, double hz, double nu, int lower_slot, int upper_slot, int nslots, int64_t ncell, int psi_pts,
+    double hx, double hz, double nu, int lower_slot, int upper_slot, int nslots, int64_t ncell, int psi_pts, int nle,
     const double* __restrict__ u, const double* __restrict__ psi, double* __restrict__ part) {
   __shared__ double sS[kMaxQ * kMaxP], sNd[kMaxP], sG[kMaxQ], sW[kMaxQ];
   __shared__ double v[3 * kMaxP * kMaxP];   // [c][k][i]  y contracted
@@ -77,13 +77,26 @@ __global__ __launch_bounds__(kWsThreads) void wall_shear_cells(
   const int nq2 = nq * nq;
   // psi face of the wall: y-face s = w, points qx + nq qz, entry 2 = dpsi/dy
   const double* pw = enr < 0 ? nullptr : psi + (enr * psi_pts + psi_face_offset(nq, nq_wn, 2 + w)) * 4 + 2;
-  const double* ut = enr < 0 ? nullptr : u + ncell * 3 * np3 + enr * 3;
+  const double* ut = enr < 0 ? nullptr : u + ncell * 3 * np3 + enr * 3 * nle;
   for (int it = tid; it < 3 * nq2; it += kWsThreads) {
     const int c = it / nq2, q = it - c * nq2, qz = q / nq, qx = q - qz * nq;
     double s = 0.0;
     for (int k = 0; k < np; ++k) s += sS[qz * np + k] * t[(c * np + k) * nq + qx];
     double d = s * ihy;
-    if (pw) d += ut[c] * pw[q * 4];
+    if (pw) {
+      // psi vanishes on the wall: d/dy (psi sum_B N_B u~_B) = (sum_B N_B u~_B) dpsi/dy there, with only the
+      // four vertex functions of the wall face (bit w along y) nonzero for l = 1
+      double wt = ut[c * nle];
+      if (nle == 8) {
+        const double gx = sG[qx], gz = sG[qz];
+        wt = 0.0;
+        for (int j = 0; j < 4; ++j) {
+          const int bx = j & 1, bz = j >> 1;
+          wt += (bx ? gx : 1.0 - gx) * (bz ? gz : 1.0 - gz) * ut[c * 8 + (bx | (w << 1) | (bz << 2))];
+        }
+      }
+      d += wt * pw[q * 4];
+    }
     f[it] = scale * sW[qx] * sW[qz] * d;
   }
   __syncthreads();
@@ -137,7 +150,7 @@ int launch_wall_shear_nodes(const dg_mesh* m, const double* u, double* out, hipS
   const double* tab = m->tab_u;
   hipLaunchKernelGGL(wall_shear_cells, dim3((unsigned)ncellw), dim3(kWsThreads), 0, s, P.nx, P.ny, P.nz, m->np_u,
                      P.nq_u, P.nq_wn, tab, m->hy, m->hx, m->hz, P.nu, m->lower_slot, m->upper_slot,
-                     m->n_enr_layers, m->ncell, m->psi_pts, u, m->psi, m->ws_part);
+                     m->n_enr_layers, m->ncell, m->psi_pts, m->nle, u, m->psi, m->ws_part);
   int rc = check_hip(hipGetLastError(), "wall shear cell kernel launch");
   if (rc) return rc;
   hipLaunchKernelGGL(wall_shear_nodes_kernel, dim3((unsigned)((ncellw + 255) / 256)), dim3(256), 0, s, P.nx, P.nz,

@@ -119,8 +119,7 @@ def test_l1_unsupported_entry_points():
     mesh = Mesh(wl.mesh, draw_inputs(wl)["tau"])
     u = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
     td = torch.zeros(wl.mesh.ncell, dtype=torch.float64, device="cuda")
-    for call in (lambda: mesh.project_velocity(u), lambda: mesh.wall_shear_nodes(u),
-                 lambda: mesh.projection_step(td, u, u, 1e-3)):
+    for call in (lambda: mesh.project_velocity(u), lambda: mesh.projection_step(td, u, u, 1e-3)):
         with pytest.raises(DgError) as ei:
             call()
         assert ei.value.code == -6
@@ -332,3 +331,18 @@ def test_l1_dual_splitting_step_matches_oracle(name):
          f"{st.helmholtz.iterations}  |du|={eu:.1e} |dp|={ep:.1e}")
     assert st.projection_its > 0
     assert eu <= 1e-8 and ep <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["tiny", "k2_stretched", "k4_large_like", "k3_vandriest_lower", "k3_switch_off"])
+def test_l1_wall_shear_nodes(name):
+    """Nodal wall shear stress (Sec. 3.2) with l = 1 (the enrichment's wall-normal
+    derivative sum_B N_B u~_B dpsi/dy on the wall) at 1e-12 of the oracle."""
+    wl = CASES[name]
+    cfg = wl.mesh
+    _log(f"[gpu] l=1 wall shear nodes case={name}")
+    inp = draw_inputs(wl)
+    mesh = Mesh(cfg, inp["tau"])
+    t = mesh.wall_shear_nodes(torch.tensor(inp["u"], device="cuda")).cpu().numpy().reshape(-1)
+    ref = O.wall_shear_nodes(cfg, inp["u"], tau=inp["tau"]).reshape(-1)
+    _log(f"[gpu]   rel {_rel(t, ref):.1e}")
+    assert _rel(t, ref) <= 1e-12

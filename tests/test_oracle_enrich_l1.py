@@ -122,8 +122,6 @@ def test_l0_only_operators_refuse_l1():
     cfg = PRESETS["tiny"].mesh.with_(enrich_degree=1)
     u = np.zeros(cfg.n_vel)
     tau = np.ones(cfg.n_tau)
-    with pytest.raises(RuntimeError):
-        O.wall_shear_nodes(cfg, u, tau)
     with pytest.raises(NotImplementedError):
         OP.project(cfg, u, np.ones((cfg.n_enriched, 1)), np.ones((cfg.n_enriched, 1)))
 
@@ -334,3 +332,20 @@ def test_projection_step_l1_meets_its_equation(name):
     # the enrichment rows are not trivially zero
     n = cfg.ncell * 3 * (cfg.k_u + 1) ** 3
     assert np.abs(x[n:]).max() > 1e-3 * np.abs(x[:n]).max()
+
+
+@pytest.mark.parametrize("name", ["tiny_spalding", "k3_lower_only"])
+def test_wall_shear_nodes_l1(name):
+    """The nodal wall shear stress (Sec. 3.2) with l = 1: eight equal vertex
+    coefficients give the l = 0 result, and with psi = y+ the enriched field
+    gives that of its polynomial equivalent on the mesh without enrichment."""
+    wl = CASES_POU[name]
+    cfg0 = wl.mesh
+    cfg1 = cfg0.with_(enrich_degree=1)
+    inp = draw_inputs(wl)
+    t0 = O.wall_shear_nodes(cfg0, inp["u"], tau=inp["tau"])
+    t1 = O.wall_shear_nodes(cfg1, _rep8(cfg0, inp["u"]), tau=inp["tau"])
+    assert np.abs(t1 - t0).max() <= 1e-13 * np.abs(t0).max()
+    base, cfg_p, u_e, u_p, _, tau = _linear_psi_setup(3, 1.1, 60)
+    te, tp = O.wall_shear_nodes(base, u_e, tau=tau), O.wall_shear_nodes(cfg_p, u_p)
+    assert np.abs(te - tp).max() < 1e-12 * np.abs(tp).max()
