@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import enriched_cells, gauss, gauss_lobatto, lagrange, require_l0, vertex_eta
+from . import enriched_cells, gauss, gauss_lobatto, lagrange, vertex_eta
 
 
 def volume_rule(cfg):
@@ -62,8 +62,8 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
     """u_new of eq. l2.  psi_old, psi_new: [nenr][npts] values at the enriched
     volume rule.  With return_cond, also the 2-norm condition number of each
     enriched cell's mass matrix.  only: enriched-cell positions to project
-    (the projection is cell-local; the others keep u_old)."""
-    require_l0(cfg)
+    (the projection is cell-local; the others keep u_old).  With l = 1 the
+    old and new enrichment functions are psi N_B (Sec. 3.1 eq. enrichment)."""
     if cfg.wall_amp != 0.0:
         raise ValueError("flat meshes only")
     n3 = (cfg.k_u + 1) ** 3
@@ -76,6 +76,7 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
     off = cfg.ncell * 3 * n3
     conds = np.zeros(len(cells))
     todo = range(len(cells)) if only is None else sorted(set(int(k) for k in only))
+    nle = _nle(cfg)
     for k in todo:
         e = cells[k]
         w, Phi, uq, on = _l2_cell(cfg, k, u_old, psi_old[k], psi_new[k], V, wts, eta, cells)
@@ -85,7 +86,7 @@ def project(cfg, u_old, psi_old, psi_new, return_cond=False, only=None):
         for c in range(3):
             x = np.linalg.lstsq(A, sw * uq[c], rcond=None)[0]
             u_new[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] = x[:n3]
-            u_new[off + 3 * k + c] = x[n3] if on else 0.0
+            u_new[off + nle * (3 * k + c):off + nle * (3 * k + c + 1)] = x[n3:] if on else 0.0
     return (u_new, conds) if return_cond else u_new
 
 
@@ -101,13 +102,15 @@ def _l2_cell(cfg, k, u_old, psi_old_k, psi_new_k, V, wts, eta, cells):
     detJ = hx * (eta[ey + 1] - eta[ey]) * hz
     w = wts * detJ
     po, pn = np.asarray(psi_old_k, dtype=float), np.asarray(psi_new_k, dtype=float)
+    nle = _nle(cfg)
+    Nl = _vertex_fns(volume_rule(cfg)[0]) if nle == 8 else np.ones((len(po), 1))   # N^l_B at the points
     on = bool(np.any(pn != 0.0))
-    Phi = np.hstack([V, pn[:, None]]) if on else V           # new local basis at the points
+    Phi = np.hstack([V, pn[:, None] * Nl]) if on else V      # new local basis at the points
     uq = []
     for c in range(3):
         ub = u_old[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
-        ut = u_old[off + 3 * k + c]
-        uq.append(V @ ub + po * ut)                          # u_old at the points
+        ut = u_old[off + nle * (3 * k + c):off + nle * (3 * k + c + 1)]
+        uq.append(V @ ub + po * (Nl @ ut))                   # u_old at the points
     return w, Phi, uq, on
 
 
@@ -115,7 +118,6 @@ def l2_normal_equation(cfg, k, u_old, psi_old_k, psi_new_k):
     """Eq. l2 of enriched cell k written as its normal equation A x_c = b_c per
     component c: A = Phi^T W Phi (the new local mass matrix), b_c = Phi^T W u_old,c,
     and babs_c = |Phi|^T W |u_old,c| (a bound on the rounding of b_c)."""
-    require_l0(cfg)
     cells = enriched_cells(cfg)
     pts, wts = volume_rule(cfg)
     V = basis_at(cfg, pts)

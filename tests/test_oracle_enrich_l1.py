@@ -118,14 +118,6 @@ def test_l1_enrichment_with_linear_psi_reduces_to_polynomial_path(k, gamma):
         assert np.abs(rt[i] - exp).max() < 1e-11 * np.abs(exp).max() + 1e-12 * scale * pn.max()
 
 
-def test_l0_only_operators_refuse_l1():
-    cfg = PRESETS["tiny"].mesh.with_(enrich_degree=1)
-    u = np.zeros(cfg.n_vel)
-    tau = np.ones(cfg.n_tau)
-    with pytest.raises(NotImplementedError):
-        OP.project(cfg, u, np.ones((cfg.n_enriched, 1)), np.ones((cfg.n_enriched, 1)))
-
-
 def _rep8(cfg0, v):
     n = cfg0.ncell * 3 * (cfg0.k_u + 1) ** 3
     return np.concatenate([v[:n], np.repeat(v[n:].reshape(-1, 3)[:, :, None], 8, axis=2).ravel()])
@@ -349,3 +341,47 @@ def test_wall_shear_nodes_l1(name):
     base, cfg_p, u_e, u_p, _, tau = _linear_psi_setup(3, 1.1, 60)
     te, tp = O.wall_shear_nodes(base, u_e, tau=tau), O.wall_shear_nodes(cfg_p, u_p)
     assert np.abs(te - tp).max() < 1e-12 * np.abs(tp).max()
+
+
+def test_l2_projection_l1_same_space_and_reproduction():
+    """Eq. l2 with l = 1: the same space reproduces u_old, and with psi_new =
+    a psi_old + p (p linear in y, so p N_B stays in Q_k) the field u_bar +
+    psi_old sum_B N_B u~_B, which is (u_bar - p sum_B N_B u~_B / a) + psi_new
+    sum_B N_B u~_B / a, comes back with u~_new = u~_old / a and that
+    polynomial part (p N_B u~_B interpolated at the nodes)."""
+    wl = CASES_POU["tiny_spalding"]
+    cfg = wl.mesh.with_(enrich_degree=1)
+    inp = draw_inputs(wl)
+    rng = np.random.default_rng(76)
+    u = rng.uniform(-1, 1, cfg.n_vel)
+    cells = O.enriched_cells(cfg)
+    ps0 = O.psi_volume(cfg, cells, tau=inp["tau"])
+    un = OP.project(cfg, u, ps0, ps0)
+    assert np.abs(un - u).max() <= 1e-10 * np.abs(u).max()
+    a = 1.6
+    pts, _ = OP.volume_rule(cfg)
+    eta = O.vertex_eta(cfg)
+    ps1 = np.empty_like(ps0)
+    for k, e in enumerate(cells):
+        ey = (e // cfg.nx) % cfg.ny
+        y = eta[ey] + (eta[ey + 1] - eta[ey]) * pts[:, 1]
+        ps1[k] = a * ps0[k] + 0.3 + 0.2 * y
+    un = OP.project(cfg, u, ps0, ps1)
+    n = cfg.k_u + 1
+    n3 = n ** 3
+    off = cfg.ncell * 3 * n3
+    nodes = O.gauss_lobatto(n)
+    for k, e in enumerate(cells):
+        ey = (e // cfg.nx) % cfg.ny
+        ut0 = u[off + 24 * k:off + 24 * (k + 1)].reshape(3, 8)
+        np.testing.assert_allclose(un[off + 24 * k:off + 24 * (k + 1)], (ut0 / a).ravel(), rtol=1e-9, atol=1e-11)
+        pn = np.zeros((8, n3))
+        for m in range(n):
+            for j in range(n):
+                for i in range(n):
+                    y = eta[ey] + (eta[ey + 1] - eta[ey]) * nodes[j]
+                    for b in range(8):
+                        pn[b, i + n * (j + n * m)] = (0.3 + 0.2 * y) * _vertex_fn(b, (nodes[i], nodes[j], nodes[m]))
+        for c in range(3):
+            exp = u[(e * 3 + c) * n3:(e * 3 + c + 1) * n3] - ut0[c] @ pn / a
+            np.testing.assert_allclose(un[(e * 3 + c) * n3:(e * 3 + c + 1) * n3], exp, rtol=0, atol=1e-9)
