@@ -101,8 +101,8 @@ typedef struct {
                           /*   dg_solve_helmholtz, dg_apply_pressure_gradient,              */
                           /*   dg_apply_velocity_divergence, dg_divdiv_tau, dg_apply_divdiv, */
                           /*   dg_vorticity_rhs, dg_vorticity, dg_pressure_neumann,         */
-                          /*   dg_wall_shear_nodes and dg_dual_splitting_step;              */
-                          /*   dg_project_velocity, dg_projection_step and the batched      */
+                          /*   dg_wall_shear_nodes, dg_project_velocity and                 */
+                          /*   dg_dual_splitting_step; dg_projection_step and the batched   */
                           /*   residual return DG_ERR_UNSUPPORTED for it                    */
   int32_t omit_step_tables; /* 1: the mesh workspace leaves out the projection-step tables  */
                           /*   (per-layer spectral factors, enriched-cell couplings), so    */
@@ -181,9 +181,14 @@ int dg_update_wall_shear_nodes(dg_mesh* mesh, const double* tau_nodes, void* str
  * wall-shear update onto the current one (paper Sec. 3.2, eq. l2):
  *   (v, u_new)_e = (v, u_old)_e  for every v of the current local space,
  * per component and enriched cell, with the enriched cell's quadrature rule;
- * the local space is span{N_B} plus psi_new while the cell's enrichment is
- * on, the polynomials alone while it is off.  Cells without enrichment are
- * copied.  Before any update (or right after setup) this is the identity up
+ * the local space is span{N_B} plus psi_new (l = 0) or the eight psi_new N_B
+ * (l = 1, N_B the trilinear vertex functions) while the cell's enrichment is
+ * on, the polynomials alone while it is off.  Solved in closed form: with
+ * r = phi - P phi (P the L2 projection onto the polynomials, phi the old and
+ * the new enrichment functions), the new enrichment coefficients solve
+ * (r_new, r_new) u~_new = (r_new, r_old) u~_old (a scalar for l = 0, an 8 x 8
+ * Cholesky solve for l = 1) and the polynomial part takes the difference of
+ * the two P phi expansions.  Cells without enrichment are copied.  Before any update (or right after setup) this is the identity up
  * to rounding.  Call it once per vector that must follow the new space, after
  * dg_update_wall_shear(_nodes) and before the next update.
  *   u_old, u_new: device, dg_num_dofs(mesh, 0) doubles each.  u_new may be

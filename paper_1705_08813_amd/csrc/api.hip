@@ -426,7 +426,6 @@ int dg_update_wall_shear_nodes(dg_mesh* m, const double* tau_nodes, void* stream
 int dg_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, void* stream) {
   if (!m || !u_old || !u_new) return set_error(DG_ERR_ARG, "mesh/u_old/u_new is NULL");
   if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "projection onto the refreshed space: flat meshes only");
-  if (m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "built for l = 0 enrichment weights only");
   if (!aligned256(u_old) || !aligned256(u_new)) return set_error(DG_ERR_ARG, "u_old and u_new must be 256-byte aligned");
   return launch_project_velocity(m, u_old, u_new, static_cast<hipStream_t>(stream));
 }

@@ -215,6 +215,113 @@ __global__ __launch_bounds__(kPrjThreads) void project_kernel(const ProjArgs A) 
   if (tid < 3) A.u_new[eo + tid] = ratio * sut[tid];
 }
 
+// Degree-1 enrichment weights (Sec. 3.1 eq. enrichment, l = 1): the eight
+// old and the eight new enrichment functions phi_B = psi N_B of the cell.
+// With a_B = K^{-1} (N, phi_B)_w and r_B = phi_B - P phi_B for both sets,
+// the new enrichment coefficients of each component solve
+//   G_new u~_new = C u~_old,  G_new = (r_new, r_new)_w,  C = (r_new, r_old)_w,
+// and u_bar_new = u_bar_old + sum_B u~_old,B a_old,B - sum_B u~_new,B a_new,B:
+// the l = 0 closed form with the scalars replaced by 8 x 8 blocks.  A cell
+// switched off in the new space gets u~_new = 0; one switched off in the old
+// space has phi_old = 0, so a_old = 0, C = 0 and u_new = u_bar_old.
+template <int NP, int NQ, int NQY>
+__global__ __launch_bounds__(kPrjThreads) void project_l1_kernel(const ProjArgs A) {
+  constexpr int NPT = NQ * NQY * NQ, NP3 = NP * NP * NP;
+  __shared__ Tab1d<NP, NQ, NQY> T;
+  __shared__ PsiPoly<NP, NQ, NQY> L;
+  __shared__ double phi[16 * NPT];  // old then new phi_B at the volume points, then r_B
+  __shared__ double ab[16 * NP3];   // a_B, old then new
+  __shared__ double GC[128];        // G_new, then C
+  __shared__ double ut[24], un[24]; // u~ old and new, [c][B] (read before any write: u_new may be u_old)
+  const int tid = threadIdx.x;
+  const int64_t enr = blockIdx.x;
+  const int64_t e = enriched_cell_index(A.nx, A.ny, A.lower_slot, A.nslots, enr);
+  load_tab1d<NP, NQ, NQY>(A.tab, A.minv, T, tid);
+  // the Gauss points of both rules follow the tables
+  const double* gx = A.tab + tab_layout(NP, NQ, NQY).size;
+  const double* gy = gx + NQ;
+  const double* po = A.psi_old + enr * A.psi_pts * 4;
+  const double* pn = A.psi_new + enr * A.psi_pts * 4;
+  for (int q = tid; q < NPT; q += kPrjThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+    const double v[3][2] = {{1.0 - gx[qx], gx[qx]}, {1.0 - gy[qy], gy[qy]}, {1.0 - gx[qz], gx[qz]}};
+    const double a = po[q * 4], b = pn[q * 4];
+#pragma unroll
+    for (int B = 0; B < 8; ++B) {
+      const double nb = v[0][B & 1] * v[1][(B >> 1) & 1] * v[2][B >> 2];
+      phi[B * NPT + q] = a * nb;
+      phi[(8 + B) * NPT + q] = b * nb;
+    }
+  }
+  const int64_t eo = A.ncell * 3 * NP3 + enr * 24;
+  if (tid < 24) ut[tid] = A.u_old[eo + tid];
+  __syncthreads();
+  for (int pr = 0; pr < 8; ++pr) {
+    const double* src[2] = {phi + 2 * pr * NPT, phi + (2 * pr + 1) * NPT};
+    psi_poly_part<2, NP, NQ, NQY, 1>(src, T, L, tid);
+    for (int i = tid; i < 2 * NP3; i += kPrjThreads) ab[2 * pr * NP3 + i] = L.b[i];
+    for (int q = tid; q < 2 * NPT; q += kPrjThreads) phi[2 * pr * NPT + q] = L.r[q];
+    __syncthreads();
+  }
+  if (tid < 128) {
+    const int j = tid & 7, i = (tid >> 3) & 7, cross = tid >> 6;  // GC[64 cross + 8 i + j]
+    const double* ri = phi + (8 + i) * NPT;
+    const double* rj = phi + (cross ? j : 8 + j) * NPT;
+    double g = 0.0;
+    for (int q = 0; q < NPT; ++q) {
+      const int qx = q % NQ, qy = (q / NQ) % NQY, qz = q / (NQ * NQY);
+      g += T.W[qx] * T.Wy[qy] * T.W[qz] * ri[q] * rj[q];
+    }
+    GC[tid] = g;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // G_new = C_h C_h^T (Cholesky), then u~_new,c = G_new^{-1} (C u~_old,c)
+    double ch[8][8] = {};
+    bool ok = A.act_new[enr] != 0;
+    for (int j = 0; j < 8 && ok; ++j) {
+      double d = GC[j * 8 + j];
+      for (int k = 0; k < j; ++k) d -= ch[j][k] * ch[j][k];
+      if (!(d > 0.0)) {
+        ok = false;
+        break;
+      }
+      ch[j][j] = sqrt(d);
+      for (int i = j + 1; i < 8; ++i) {
+        double v = GC[i * 8 + j];
+        for (int k = 0; k < j; ++k) v -= ch[i][k] * ch[j][k];
+        ch[i][j] = v / ch[j][j];
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      double y[8];
+      for (int i = 0; i < 8; ++i) {
+        double v = 0.0;
+        for (int j = 0; j < 8; ++j) v += GC[64 + i * 8 + j] * ut[c * 8 + j];
+        for (int k = 0; k < i; ++k) v -= ch[i][k] * y[k];
+        y[i] = ok ? v / ch[i][i] : 0.0;
+      }
+      for (int i = 7; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < 8; ++k) v -= ch[k][i] * un[c * 8 + k];
+        un[c * 8 + i] = ok ? v / ch[i][i] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  // each entry is read and written by the same thread, so u_new may alias u_old
+  const double* ub = A.u_old + e * 3 * NP3;
+  double* vb = A.u_new + e * 3 * NP3;
+  for (int it = tid; it < 3 * NP3; it += kPrjThreads) {
+    const int c = it / NP3, B = it - c * NP3;
+    double v = ub[it];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) v += ut[c * 8 + b] * ab[b * NP3 + B] - un[c * 8 + b] * ab[(8 + b) * NP3 + B];
+    vb[it] = v;
+  }
+  if (tid < 24) A.u_new[eo + tid] = un[tid];
+}
+
 // ---------------------------------------------------------------------------
 // Inverse velocity mass matrix, x = M^{-1} r (M du/dt = -R(u)).
 //
@@ -857,7 +964,10 @@ int launch_project_velocity(const dg_mesh* m, const double* u_old, double* u_new
   A.u_new = u_new;
 #define X(p, q, w)                                                                                  \
   if (m->np_u == p && m->P.nq_u == q && m->P.nq_wn == w) {                                          \
-    hipLaunchKernelGGL((project_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
+    if (m->nle == 8)                                                                                \
+      hipLaunchKernelGGL((project_l1_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
+    else                                                                                            \
+      hipLaunchKernelGGL((project_kernel<p, q, w>), dim3((unsigned)m->nenr), dim3(kPrjThreads), 0, s, A); \
     return check_hip(hipGetLastError(), "projection kernel launch");                                \
   }
   DG_PRJ_COMBOS(X)
