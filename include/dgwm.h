@@ -291,11 +291,13 @@ int dg_apply_inverse_mass(const dg_mesh* mesh, const double* r, double* x, void*
  * for l = 0 or psi N_B e_c over the eight vertex functions for l = 1), {{p}}
  * the central average of the two traces, on no-slip walls the
  * interior value {{p}} = p- (Sec. 4.2, projection step).  Velocity quadrature of the cell (nq_u^3, nq_u x
- * nq_wn x nq_u in enriched cells) and of its faces.  Flat meshes only.
+ * nq_wn x nq_u in enriched cells) and of its faces.  On the curved-wall mesh
+ * (l = 0) the geometry enters per point (J^{-1}, |det J| and the curved
+ * normals of the isoparametric cells).
  *   p: device, dg_num_dofs(mesh, 1) doubles; g: device, dg_num_dofs(mesh, 0)
  *   doubles (velocity layout, enrichment rows included), distinct from p.
- *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall or a degree
- *   combination not compiled), DG_ERR_HIP. */
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (a degree combination not
+ *   compiled), DG_ERR_HIP. */
 int dg_apply_pressure_gradient(const dg_mesh* mesh, const double* p, double* g, void* stream);
 
 /* Velocity divergence term (paper Sec. 4.2):
@@ -305,7 +307,8 @@ int dg_apply_pressure_gradient(const dg_mesh* mesh, const double* p, double* g, 
  * on no-slip walls the interior value {{u}} = u- (Sec. 4.2, the boundary
  * condition of this term in the pressure Poisson equation); the same
  * quadrature as the gradient, so that q^T C u = -u^T P q wherever the rules
- * integrate div(q u) exactly and q vanishes on the walls.  Flat meshes only.
+ * integrate div(q u) exactly and q vanishes on the walls.  Curved-wall meshes
+ * (l = 0) as for dg_apply_pressure_gradient.
  *   u: device, dg_num_dofs(mesh, 0) doubles; c: device, dg_num_dofs(mesh, 1)
  *   doubles (pressure layout), distinct from u.
  *   Errors: as for dg_apply_pressure_gradient. */

@@ -439,7 +439,6 @@ int dg_apply_inverse_mass(const dg_mesh* m, const double* r, double* x, void* st
 
 int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, void* stream) {
   if (!m || !p || !g) return set_error(DG_ERR_ARG, "mesh/p/g is NULL");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "pressure gradient: flat meshes only");
   if (static_cast<const void*>(p) == static_cast<const void*>(g)) return set_error(DG_ERR_ARG, "p and g must not alias");
   if (!aligned256(p) || !aligned256(g)) return set_error(DG_ERR_ARG, "p and g must be 256-byte aligned");
   return launch_divgrad(m, false, p, g, static_cast<hipStream_t>(stream));
@@ -447,7 +446,6 @@ int dg_apply_pressure_gradient(const dg_mesh* m, const double* p, double* g, voi
 
 int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, void* stream) {
   if (!m || !u || !c) return set_error(DG_ERR_ARG, "mesh/u/c is NULL");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "velocity divergence: flat meshes only");
   if (static_cast<const void*>(u) == static_cast<const void*>(c)) return set_error(DG_ERR_ARG, "u and c must not alias");
   if (!aligned256(u) || !aligned256(c)) return set_error(DG_ERR_ARG, "u and c must be 256-byte aligned");
   return launch_divgrad(m, true, u, c, static_cast<hipStream_t>(stream));

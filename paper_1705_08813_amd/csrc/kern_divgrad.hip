@@ -469,6 +469,7 @@ __global__ __launch_bounds__(kDgThreads) void gradient_kernel(const DgArgs A, in
 #define DG_DG_COMBOS(X) X(3, 2, 4, 8) X(3, 2, 4, 4) X(4, 3, 4, 8) X(4, 3, 5, 8) X(4, 3, 5, 5) X(5, 4, 7, 8) X(6, 5, 8, 8)
 
 int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s) {
+  if (m->curved) return launch_divgrad_curved(m, divergence, in, out, s);
   DgArgs A;
   A.nx = m->P.nx;
   A.ny = m->P.ny;

@@ -1,0 +1,418 @@
+// Pressure gradient and velocity divergence terms of the dual-splitting
+// scheme (arXiv 1705.08813, Sec. 4.2) on the curved-wall mesh, FP64:
+//
+//   P: g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}     (velocity test functions)
+//   C: c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}    (pressure test functions)
+//
+// with the interior values on the no-slip walls, the full velocity (psi u~
+// in enriched cells, l = 0) and the enrichment test functions psi e_c, as on
+// flat meshes.  Every cell is mapped isoparametrically, so the geometry
+// enters point by point from the mesh's geometry table (J^{-1} and the
+// weight w |det J| at the volume points; w |det J| |J^{-T} e_d| at the face
+// points, the outward normal being +-J^{-T} e_d normalised): with
+// d_c N = sum_a J^{-1}[a][c] d_a N,
+//
+//   P volume:  g(N_B e_c) -= sum_q sum_a d_a N_B(q) F_ac(q),  F_ac = w|J| J^{-1}[a][c] p(q),
+//   C volume:  c(N^p_B)   -= sum_q sum_a d_a N^p_B(q) F_a(q), F_a = w|J| sum_d J^{-1}[a][d] u_d(q),
+//
+// and the face terms integrate the face-layer basis functions (the
+// Gauss-Lobatto nodal basis has its face values on that layer) against
+// w dA n {{p}} or w dA {{u}} . n at the face points.  One workgroup per cell
+// with the cell's block accumulated in LDS and written once; the 1-D tables
+// of both bases at both rules are compile-time constants.  Cost is not the
+// concern here (the curved configuration's hot path is the velocity
+// operator): the contractions are direct sums over the points.
+#include "ctab.h"
+#include "kern_common.h"
+
+namespace dgwm {
+
+namespace {
+
+constexpr int kCvThreads = 256;
+
+struct CvArgs {
+  int nx, ny, nz, lower_slot, upper_slot, nslots, psi_pts, geo_stride, fully_periodic;
+  int64_t ncell;
+  const double* geo;  // [cell][geo_stride][J^{-1} (9), weight]
+  const double* psi;  // [enr][psi_pts][4]: psi, grad psi (physical)
+  const double* in;   // p (gradient) or u (divergence)
+  double* out;
+};
+
+struct CvCell {
+  int i[3];
+  int64_t e, enr;
+};
+
+__device__ __forceinline__ int64_t cv_enr(const CvArgs& A, int ex, int ey, int ez) {
+  if (A.fully_periodic) return -1;
+  int slot = -1;
+  if (ey == 0 && A.lower_slot >= 0) slot = A.lower_slot;
+  else if (ey == A.ny - 1 && A.upper_slot >= 0) slot = A.upper_slot;
+  return slot < 0 ? -1 : ex + (int64_t)A.nx * (slot + (int64_t)A.nslots * ez);
+}
+
+// Regular cells: b = ex + nx (ly + nlayers ez), ey = layer_lo + ly; enriched
+// cells: b = enriched index.
+template <bool ENR>
+__device__ __forceinline__ CvCell cv_cell(const CvArgs& A, int64_t b, int layer_lo, int nlayers) {
+  CvCell c;
+  c.i[0] = (int)(b % A.nx);
+  const int64_t t0 = b / A.nx;
+  if (ENR) {
+    const int slot = (int)(t0 % A.nslots);
+    c.i[2] = (int)(t0 / A.nslots);
+    c.i[1] = slot == A.lower_slot ? 0 : A.ny - 1;
+  } else {
+    c.i[1] = layer_lo + (int)(t0 % nlayers);
+    c.i[2] = (int)(t0 / nlayers);
+  }
+  c.e = c.i[0] + (int64_t)A.nx * (c.i[1] + (int64_t)A.ny * c.i[2]);
+  c.enr = ENR ? b : -1;
+  return c;
+}
+
+// Neighbour across face (d, s) and its enriched index (-1: none); -1 on a wall.
+__device__ __forceinline__ int64_t cv_neighbour(const CvArgs& A, const CvCell& c, int d, int s, int64_t& nenr) {
+  int i[3] = {c.i[0], c.i[1], c.i[2]};
+  const int n[3] = {A.nx, A.ny, A.nz};
+  int j = i[d] + (s ? 1 : -1);
+  nenr = -1;
+  if (j < 0 || j >= n[d]) {
+    if (d == 1 && !A.fully_periodic) return -1;
+    j = j < 0 ? j + n[d] : j - n[d];
+  }
+  i[d] = j;
+  nenr = cv_enr(A, i[0], i[1], i[2]);
+  return i[0] + (int64_t)A.nx * (i[1] + (int64_t)A.ny * i[2]);
+}
+
+// Node of position (l1, l2) on the layer of face (d, s) of an NP^3 block.
+template <int NP>
+__device__ __forceinline__ int cv_layer(int d, int s, int l1, int l2) {
+  const int ld = s ? NP - 1 : 0;
+  if (d == 0) return ld + NP * (l1 + NP * l2);
+  if (d == 1) return l1 + NP * (ld + NP * l2);
+  return l1 + NP * (l2 + NP * ld);
+}
+
+// Fixed-order block sum of NV values per thread.
+template <int NV>
+__device__ __forceinline__ void cv_block_sum(double (&v)[NV], double* red, int tid) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
+  constexpr int NW = kCvThreads / 64;
+  __syncthreads();
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k * NW + (tid >> 6)] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    v[k] = 0.0;
+    for (int w = 0; w < NW; ++w) v[k] += red[k * NW + w];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P: g = P p (velocity layout).
+template <int NPU, int NPP, int NQ, int NQY, bool ENR>
+__global__ __launch_bounds__(kCvThreads) void curved_gradient_kernel(const CvArgs A, int layer_lo, int nlayers) {
+  constexpr int QY = ENR ? NQY : NQ;  // the cell's wall-normal rule
+  constexpr int NU3 = NPU * NPU * NPU, NP3 = NPP * NPP * NPP, NPT = NQ * QY * NQ;
+  constexpr int FMAX = NQ * (QY > NQ ? QY : NQ);
+  constexpr auto& ux = ct::tab<NPU, NQ>;
+  constexpr auto& uy = ct::tab<NPU, QY>;
+  constexpr auto& px = ct::tab<NPP, NQ>;
+  constexpr auto& py = ct::tab<NPP, QY>;
+  __shared__ double sp[NP3];
+  __shared__ double snb[6][NPP * NPP];
+  __shared__ double F[9][NPT];
+  __shared__ double G[3][FMAX];
+  __shared__ double acc[3 * NU3];
+  __shared__ double red[3 * (kCvThreads / 64)];
+  __shared__ int64_t nbs[6];
+  const int tid = threadIdx.x;
+  const CvCell c = cv_cell<ENR>(A, blockIdx.x, layer_lo, nlayers);
+  if (tid < 6) {
+    int64_t ne;
+    nbs[tid] = cv_neighbour(A, c, tid / 2, tid % 2, ne);
+  }
+  for (int k = tid; k < NP3; k += kCvThreads) sp[k] = A.in[c.e * NP3 + k];
+  __syncthreads();
+  for (int k = tid; k < 6 * NPP * NPP; k += kCvThreads) {
+    const int f = k / (NPP * NPP), l = k - f * NPP * NPP;
+    const int64_t nb = nbs[f];
+    // the neighbour's layer on the shared face is its face (d, 1 - s)
+    snb[f][l] = nb >= 0 ? A.in[nb * NP3 + cv_layer<NPP>(f / 2, 1 - f % 2, l % NPP, l / NPP)] : 0.0;
+  }
+  const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
+  const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
+  double ev[3] = {0.0, 0.0, 0.0};  // enrichment rows (thread partials)
+  for (int q = tid; q < NPT; q += kCvThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
+    double v = 0.0;
+    for (int k = 0; k < NPP; ++k)
+      for (int j = 0; j < NPP; ++j) {
+        const double fy = py.S[qy][j] * px.S[qz][k];
+        for (int i = 0; i < NPP; ++i) v += px.S[qx][i] * fy * sp[i + NPP * (j + NPP * k)];
+      }
+    const double* g = geo + q * 10;
+    const double wv = g[9] * v;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) F[a][q] = wv * g[a];  // F[3a + c] = w|J| J^{-1}[a][c] p
+    if (ENR)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) ev[cc] -= g[9] * ps[q * 4 + 1 + cc] * v;
+  }
+  __syncthreads();
+  for (int it = tid; it < 3 * NU3; it += kCvThreads) {
+    const int cc = it / NU3, B = it - cc * NU3;
+    const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
+    double s = 0.0;
+    for (int qz = 0; qz < NQ; ++qz)
+      for (int qy = 0; qy < QY; ++qy) {
+        const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
+        const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
+        for (int qx = 0; qx < NQ; ++qx) {
+          const int q = qx + NQ * (qy + QY * qz);
+          s += ux.Sd[qx][i] * yz * F[0 + cc][q] + ux.S[qx][i] * dyz * F[3 + cc][q] + ux.S[qx][i] * ydz * F[6 + cc][q];
+        }
+      }
+    acc[it] = -s;
+  }
+  __syncthreads();
+  for (int f = 0; f < 6; ++f) {
+    const int d = f / 2, s = f % 2;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const int Q1 = t1 == 1 ? QY : NQ, Q2 = t2 == 1 ? QY : NQ;
+    const int off = psi_face_offset(NQ, QY, f);
+    const bool wall = nbs[f] < 0;
+    for (int k = tid; k < Q1 * Q2; k += kCvThreads) {
+      const int q1 = k % Q1, q2 = k / Q1;
+      double pm = 0.0, pp = 0.0;
+      for (int l2 = 0; l2 < NPP; ++l2) {
+        const double b2 = t2 == 1 ? py.S[q2][l2] : px.S[q2][l2];
+        for (int l1 = 0; l1 < NPP; ++l1) {
+          const double b = (t1 == 1 ? py.S[q1][l1] : px.S[q1][l1]) * b2;
+          pm += b * sp[cv_layer<NPP>(d, s, l1, l2)];
+          pp += b * snb[f][l1 + NPP * l2];
+        }
+      }
+      const double pavg = wall ? pm : 0.5 * (pm + pp);
+      const double* g = geo + (off + k) * 10;
+      const double nrm = sqrt(g[3 * d] * g[3 * d] + g[3 * d + 1] * g[3 * d + 1] + g[3 * d + 2] * g[3 * d + 2]);
+      const double sc = (s ? 1.0 : -1.0) * g[9] * pavg / nrm;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        G[cc][k] = sc * g[3 * d + cc];  // w dA n_c {{p}}
+        if (ENR) ev[cc] += ps[(off + k) * 4] * G[cc][k];
+      }
+    }
+    __syncthreads();
+    for (int it = tid; it < 3 * NPU * NPU; it += kCvThreads) {
+      const int cc = it / (NPU * NPU), l = it - cc * NPU * NPU, l1 = l % NPU, l2 = l / NPU;
+      double v = 0.0;
+      for (int q2 = 0; q2 < Q2; ++q2) {
+        const double b2 = t2 == 1 ? uy.S[q2][l2] : ux.S[q2][l2];
+        for (int q1 = 0; q1 < Q1; ++q1) v += (t1 == 1 ? uy.S[q1][l1] : ux.S[q1][l1]) * b2 * G[cc][q1 + Q1 * q2];
+      }
+      acc[cc * NU3 + cv_layer<NPU>(d, s, l1, l2)] += v;
+    }
+    __syncthreads();
+  }
+  double* o = A.out + c.e * 3 * NU3;
+  for (int it = tid; it < 3 * NU3; it += kCvThreads) o[it] = acc[it];
+  if (ENR) {
+    cv_block_sum<3>(ev, red, tid);
+    if (tid < 3) A.out[A.ncell * 3 * NU3 + c.enr * 3 + tid] = ev[tid];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C: c = C u (pressure layout).
+template <int NPU, int NPP, int NQ, int NQY, bool ENR>
+__global__ __launch_bounds__(kCvThreads) void curved_divergence_kernel(const CvArgs A, int layer_lo, int nlayers) {
+  constexpr int QY = ENR ? NQY : NQ;
+  constexpr int NU3 = NPU * NPU * NPU, NU2 = NPU * NPU, NP3 = NPP * NPP * NPP, NPT = NQ * QY * NQ;
+  constexpr int FMAX = NQ * (QY > NQ ? QY : NQ);
+  constexpr auto& ux = ct::tab<NPU, NQ>;
+  constexpr auto& uy = ct::tab<NPU, QY>;
+  constexpr auto& px = ct::tab<NPP, NQ>;
+  constexpr auto& py = ct::tab<NPP, QY>;
+  __shared__ double su[3 * NU3];
+  __shared__ double snb[6][3 * NU2];
+  __shared__ double F[3][NPT];
+  __shared__ double G[FMAX];
+  __shared__ double acc[NP3];
+  __shared__ double sut[3], snut[6][3];
+  __shared__ int64_t nbs[6], nbe[6];
+  const int tid = threadIdx.x;
+  const CvCell c = cv_cell<ENR>(A, blockIdx.x, layer_lo, nlayers);
+  const int64_t n_poly = A.ncell * 3 * NU3;
+  if (tid < 6) {
+    int64_t ne;
+    nbs[tid] = cv_neighbour(A, c, tid / 2, tid % 2, ne);
+    nbe[tid] = ne;
+  }
+  for (int k = tid; k < 3 * NU3; k += kCvThreads) su[k] = A.in[c.e * 3 * NU3 + k];
+  if (tid < 3) sut[tid] = ENR ? A.in[n_poly + c.enr * 3 + tid] : 0.0;
+  __syncthreads();
+  for (int k = tid; k < 6 * 3 * NU2; k += kCvThreads) {
+    const int f = k / (3 * NU2), r = k - f * 3 * NU2, cc = r / NU2, l = r - cc * NU2;
+    const int64_t nb = nbs[f];
+    snb[f][r] = nb >= 0 ? A.in[nb * 3 * NU3 + cc * NU3 + cv_layer<NPU>(f / 2, 1 - f % 2, l % NPU, l / NPU)] : 0.0;
+  }
+  if (tid < 18) {
+    const int f = tid / 3, cc = tid % 3;
+    snut[f][cc] = (nbs[f] >= 0 && nbe[f] >= 0) ? A.in[n_poly + nbe[f] * 3 + cc] : 0.0;
+  }
+  const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
+  const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
+  for (int q = tid; q < NPT; q += kCvThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < NPU; ++k)
+      for (int j = 0; j < NPU; ++j) {
+        const double fy = uy.S[qy][j] * ux.S[qz][k];
+        for (int i = 0; i < NPU; ++i) {
+          const double b = ux.S[qx][i] * fy;
+          const int B = i + NPU * (j + NPU * k);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) u[d] += b * su[d * NU3 + B];
+        }
+      }
+    if (ENR)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) u[d] += ps[q * 4] * sut[d];
+    const double* g = geo + q * 10;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a][q] = g[9] * (g[3 * a] * u[0] + g[3 * a + 1] * u[1] + g[3 * a + 2] * u[2]);
+  }
+  __syncthreads();
+  for (int B = tid; B < NP3; B += kCvThreads) {
+    const int i = B % NPP, j = (B / NPP) % NPP, k = B / (NPP * NPP);
+    double s = 0.0;
+    for (int qz = 0; qz < NQ; ++qz)
+      for (int qy = 0; qy < QY; ++qy) {
+        const double yz = py.S[qy][j] * px.S[qz][k], dyz = py.Sd[qy][j] * px.S[qz][k];
+        const double ydz = py.S[qy][j] * px.Sd[qz][k];
+        for (int qx = 0; qx < NQ; ++qx) {
+          const int q = qx + NQ * (qy + QY * qz);
+          s += px.Sd[qx][i] * yz * F[0][q] + px.S[qx][i] * dyz * F[1][q] + px.S[qx][i] * ydz * F[2][q];
+        }
+      }
+    acc[B] = -s;
+  }
+  __syncthreads();
+  for (int f = 0; f < 6; ++f) {
+    const int d = f / 2, s = f % 2;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const int Q1 = t1 == 1 ? QY : NQ, Q2 = t2 == 1 ? QY : NQ;
+    const int off = psi_face_offset(NQ, QY, f);
+    const int64_t nb = nbs[f], ne = nbe[f];
+    // the neighbour's face (d, 1 - s) in its own point layout (an enriched neighbour across an
+    // x- or z-face shares this cell's rule; across a y-face both tangential rules are nq)
+    const int noff = psi_face_offset(NQ, NQY, 2 * d + 1 - s);
+    for (int k = tid; k < Q1 * Q2; k += kCvThreads) {
+      const int q1 = k % Q1, q2 = k / Q1;
+      double um[3] = {0.0, 0.0, 0.0}, up[3] = {0.0, 0.0, 0.0};
+      for (int l2 = 0; l2 < NPU; ++l2) {
+        const double b2 = t2 == 1 ? uy.S[q2][l2] : ux.S[q2][l2];
+        for (int l1 = 0; l1 < NPU; ++l1) {
+          const double b = (t1 == 1 ? uy.S[q1][l1] : ux.S[q1][l1]) * b2;
+          const int node = cv_layer<NPU>(d, s, l1, l2);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            um[cc] += b * su[cc * NU3 + node];
+            up[cc] += b * snb[f][cc * NU2 + l1 + NPU * l2];
+          }
+        }
+      }
+      if (ENR) {
+        const double pm = ps[(off + k) * 4];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) um[cc] += pm * sut[cc];
+      }
+      if (nb >= 0 && ne >= 0) {
+        const double pn = A.psi[(ne * (int64_t)A.psi_pts + noff + k) * 4];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) up[cc] += pn * snut[f][cc];
+      }
+      const double* g = geo + (off + k) * 10;
+      const double nrm = sqrt(g[3 * d] * g[3 * d] + g[3 * d + 1] * g[3 * d + 1] + g[3 * d + 2] * g[3 * d + 2]);
+      double un = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) un += (nb >= 0 ? 0.5 * (um[cc] + up[cc]) : um[cc]) * g[3 * d + cc];
+      G[k] = (s ? 1.0 : -1.0) * g[9] * un / nrm;  // w dA {{u}} . n
+    }
+    __syncthreads();
+    for (int l = tid; l < NPP * NPP; l += kCvThreads) {
+      const int l1 = l % NPP, l2 = l / NPP;
+      double v = 0.0;
+      for (int q2 = 0; q2 < Q2; ++q2) {
+        const double b2 = t2 == 1 ? py.S[q2][l2] : px.S[q2][l2];
+        for (int q1 = 0; q1 < Q1; ++q1) v += (t1 == 1 ? py.S[q1][l1] : px.S[q1][l1]) * b2 * G[q1 + Q1 * q2];
+      }
+      acc[cv_layer<NPP>(d, s, l1, l2)] += v;
+    }
+    __syncthreads();
+  }
+  for (int B = tid; B < NP3; B += kCvThreads) A.out[c.e * NP3 + B] = acc[B];
+}
+
+}  // namespace
+
+// (k_u+1, k_p+1, nq_u, nq_wn) combinations: the velocity ones with k_p = k_u - 1
+#define DG_CV_COMBOS(X) X(3, 2, 4, 8) X(3, 2, 4, 4) X(4, 3, 4, 8) X(4, 3, 5, 8) X(4, 3, 5, 5) X(5, 4, 7, 8) X(6, 5, 8, 8)
+
+int launch_divgrad_curved(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s) {
+  CvArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.upper_slot = m->upper_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  A.geo_stride = m->geo_stride;
+  A.fully_periodic = m->P.fully_periodic;
+  A.ncell = m->ncell;
+  A.geo = m->geo;
+  A.psi = m->psi;
+  A.in = in;
+  A.out = out;
+  if (!m->geo || m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "curved P / C: l = 0 enrichment only");
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
+  const bool any_w = m->nenr == 0;
+  const int nqw = m->P.nq_wn;
+#define LAUNCH(KER, pu, pp, q, w, ENRV, grid, lo_, nl_) \
+  hipLaunchKernelGGL((KER<pu, pp, q, w, ENRV>), dim3((unsigned)(grid)), dim3(kCvThreads), 0, s, A, lo_, nl_)
+#define X(pu, pp, q, w)                                                                               \
+  if (m->np_u == pu && m->np_p == pp && m->P.nq_u == q && (any_w || nqw == w)) {                      \
+    if (nreg > 0) {                                                                                   \
+      if (divergence) LAUNCH(curved_divergence_kernel, pu, pp, q, w, false, nreg, lo, nl);            \
+      else LAUNCH(curved_gradient_kernel, pu, pp, q, w, false, nreg, lo, nl);                         \
+      const int rc = check_hip(hipGetLastError(), "curved divergence/gradient kernel launch");        \
+      if (rc) return rc;                                                                              \
+    }                                                                                                 \
+    if (m->nenr > 0) {                                                                                \
+      if (divergence) LAUNCH(curved_divergence_kernel, pu, pp, q, w, true, m->nenr, 0, 0);            \
+      else LAUNCH(curved_gradient_kernel, pu, pp, q, w, true, m->nenr, 0, 0);                         \
+    }                                                                                                 \
+    return check_hip(hipGetLastError(), "curved divergence/gradient kernel launch");                  \
+  }
+  DG_CV_COMBOS(X)
+#undef X
+#undef LAUNCH
+  return set_error(DG_ERR_UNSUPPORTED,
+                   "curved pressure gradient / velocity divergence: (k_u+1, k_p+1, nq_u, nq_wn) combination not compiled");
+}
+
+}  // namespace dgwm

@@ -111,11 +111,63 @@ def test_large_mesh_sampled():
     assert _rel(g[erows], go[erows]) <= TOL
 
 
-def test_divgrad_rejects_curved_mesh():
-    mesh = Mesh(MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3))
-    with pytest.raises(DgError) as ei:
-        mesh.apply_pressure_gradient(torch.zeros(mesh.n_p, dtype=torch.float64, device="cuda"))
-    assert ei.value.code == -6
-    with pytest.raises(DgError) as ei:
-        mesh.apply_velocity_divergence(torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda"))
-    assert ei.value.code == -6
+# The curved-wall mesh (Sec. 5.2 geometry: isoparametric cells, per-point
+# J^{-1} and weights from the geometry table, curved normals on the lower wall).
+CURVED = {
+    "curved_k3": MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3),
+    "curved_k5": MeshConfig(nx=3, ny=3, nz=2, wall_amp=0.3, gamma=1.2, k_u=5, nq_u=8, nq_wn=8, k_p=4, nq_p=5),
+    "curved_k4_two_layers": MeshConfig(nx=3, ny=2, nz=2, wall_amp=0.25, k_u=4, nq_u=7, nq_wn=8, k_p=3, nq_p=4),
+    "curved_k2_plain": MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=2, nq_u=4, nq_wn=4, k_p=1, nq_p=2,
+                                  enrich_lower=0, enrich_upper=0),
+    "curved_k3_lower_only": MeshConfig(nx=3, ny=3, nz=2, wall_amp=0.3, gamma=0.8, k_u=3, nq_u=5, nq_wn=8, k_p=2,
+                                       nq_p=3, enrich_upper=0),
+}
+
+
+@pytest.mark.parametrize("name", list(CURVED))
+def test_curved_gradient_and_divergence_match_oracle(name):
+    cfg = CURVED[name]
+    _log(f"[gpu] curved gradient/divergence case={name}")
+    inp = draw_inputs(Workload("dgc", cfg, 24, 0.2, 2.0))
+    mesh = Mesh(cfg, inp["tau"])
+    g = mesh.apply_pressure_gradient(torch.tensor(inp["p"], device="cuda")).cpu().numpy()
+    c = mesh.apply_velocity_divergence(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    go = O.pressure_gradient(cfg, inp["p"], tau=inp["tau"])
+    co = O.velocity_divergence(cfg, inp["u"], tau=inp["tau"])
+    n = cfg.ncell * 3 * (cfg.k_u + 1) ** 3
+    _log(f"[gpu]   grad poly {_rel(g[:n], go[:n]):.2e} enr {_rel(g[n:], go[n:]) if n < g.size else 0:.2e} "
+         f"div {_rel(c, co):.2e}")
+    assert _rel(g[:n], go[:n]) <= TOL
+    if n < g.size:
+        assert _rel(g[n:], go[n:]) <= TOL
+    assert _rel(c, co) <= TOL
+
+
+def test_curved_workload_sampled():
+    """The 48 x 24 x 24, k = 5 curved workload on sampled cells (wall rows included)."""
+    wl = PRESETS["curved"]
+    cfg = wl.mesh
+    _log("[gpu] curved gradient/divergence 48x24x24")
+    inp = draw_inputs(wl)
+    mesh = Mesh(cfg, inp["tau"])
+    g = mesh.apply_pressure_gradient(torch.tensor(inp["p"], device="cuda")).cpu().numpy()
+    c = mesh.apply_velocity_divergence(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    rng = np.random.default_rng(9)
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    cells = set(rng.integers(0, cfg.ncell, 16).tolist())
+    for ey in (0, 1, ny - 2, ny - 1):
+        for _ in range(4):
+            cells.add(int(rng.integers(0, nx)) + nx * (ey + ny * int(rng.integers(0, nz))))
+    cells = np.array(sorted(cells), dtype=np.int64)
+    go = O.pressure_gradient(cfg, inp["p"], tau=inp["tau"], cells=cells)
+    co = O.velocity_divergence(cfg, inp["u"], tau=inp["tau"], cells=cells)
+    n3, n3p = 3 * (cfg.k_u + 1) ** 3, (cfg.k_p + 1) ** 3
+    rows = (cells[:, None] * n3 + np.arange(n3)[None, :]).ravel()
+    prow = (cells[:, None] * n3p + np.arange(n3p)[None, :]).ravel()
+    _log(f"[gpu]   {len(cells)} cells: grad {_rel(g[rows], go[rows]):.2e} div {_rel(c[prow], co[prow]):.2e}")
+    assert _rel(g[rows], go[rows]) <= TOL
+    assert _rel(c[prow], co[prow]) <= TOL
+    cl = O.enriched_cells(cfg).tolist()
+    erows = np.array([cfg.ncell * n3 + 3 * cl.index(int(e)) + cc for e in cells if int(e) in cl for cc in range(3)])
+    assert erows.size > 0
+    assert _rel(g[erows], go[erows]) <= TOL
