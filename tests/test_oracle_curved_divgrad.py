@@ -1,5 +1,5 @@
-"""Pins of the oracle's pressure gradient term P and velocity divergence term
-C (Sec. 4.2) on the curved-wall mesh (lower wall y_w = -1 + a cos(2 pi x /
+"""Pins of the oracle's pressure gradient term P, velocity divergence term C
+and div-div penalty D (Sec. 4.2) on the curved-wall mesh (lower wall y_w = -1 + a cos(2 pi x /
 Lx), each column stretched linearly up to y = +1, isoparametric cells of
 degree k_u).
 
@@ -115,23 +115,43 @@ def _curved_y(cfg, x, eta):
     return yw + 0.5 * (eta + 1.0) * (1.0 - yw)
 
 
-@pytest.mark.parametrize("name", list(CURVED))
-def test_divergence_of_the_mapped_coordinate(name):
-    cfg = CURVED[name]
-    n, npp = cfg.k_u + 1, cfg.k_p + 1
+def _mapped_y(cfg):
+    """The velocity (0, y, 0), y the mapped coordinate at the nodes of every
+    cell (no enrichment part), and y per cell as [i][j] node values."""
+    n = cfg.k_u + 1
     n3 = n ** 3
-    gl, glp = _gl_nodes(n), _gl_nodes(npp)
+    gl = _gl_nodes(n)
     assert np.abs(gl - O.gauss_lobatto(n)).max() < 1e-14
     eta = O.vertex_eta(cfg)
-    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    hx = cfg.Lx / cfg.nx
     u = np.zeros(cfg.n_vel)
-    blk = u.reshape(cfg.ncell, 3, n3)
+    blk = u[:cfg.ncell * 3 * n3].reshape(cfg.ncell, 3, n3)
     Y = {}
     for e in range(cfg.ncell):
         ex, ey = e % cfg.nx, (e // cfg.nx) % cfg.ny
         X, E = np.meshgrid(ex * hx + hx * gl, eta[ey] + (eta[ey + 1] - eta[ey]) * gl, indexing="ij")  # [i][j]
         Y[e] = _curved_y(cfg, X, E)
         blk[e, 1] = np.broadcast_to(Y[e].T[None], (n, n, n)).ravel()   # [m][j][i]
+    return u, Y
+
+
+def _cell_volumes(cfg, Y):
+    """|e| = hx hz int_0^1 int_0^1 dy/dxi_y dxi_x dxi_y, y the degree-k_u interpolant of the map."""
+    n = cfg.k_u + 1
+    gq, wq = np.polynomial.legendre.leggauss(2 * n)
+    gq, wq = 0.5 * (gq + 1.0), 0.5 * wq
+    vx, dx = _lagrange(_gl_nodes(n), gq)
+    return np.array([cfg.Lx / cfg.nx * cfg.Lz / cfg.nz * wq @ np.einsum("ai,bj,ij->ab", vx, dx, Y[e]) @ wq
+                     for e in range(cfg.ncell)])
+
+
+@pytest.mark.parametrize("name", list(CURVED))
+def test_divergence_of_the_mapped_coordinate(name):
+    cfg = CURVED[name]
+    n, npp = cfg.k_u + 1, cfg.k_p + 1
+    gl, glp = _gl_nodes(n), _gl_nodes(npp)
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    u, Y = _mapped_y(cfg)
     cu = O.velocity_divergence(cfg, u)
     # int_e N^p_B dV with dV = hx hz dy/dxi_y dxi, on a Gauss rule exact for these polynomials
     gq, wq = np.polynomial.legendre.leggauss(2 * n + npp)
@@ -144,6 +164,31 @@ def test_divergence_of_the_mapped_coordinate(name):
         ref = np.einsum("a,b,c,ab,ai,bj,ck->kji", wq, wq, wq, jac, px, px, px).ravel()
         got = cu[e * npp ** 3:(e + 1) * npp ** 3]
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), e
+
+
+@pytest.mark.parametrize("name", list(CURVED))
+def test_divdiv_penalty_on_curved_cells(name):
+    """tau_D (eq. tauD) of a constant field is |U| |e|^(1/3) dt/Cr; the penalty
+    (eq. div-div) vanishes on it, is symmetric, and on the mapped-coordinate
+    field (div = 1) its cell-wise energy u^T D_e u is tau_e |e|."""
+    cfg = CURVED[name]
+    n3 = (cfg.k_u + 1) ** 3
+    uY, Y = _mapped_y(cfg)
+    vol = _cell_volumes(cfg, Y)
+    U = np.array([0.3, -0.7, 1.1])
+    uU = _const_velocity(cfg, U)
+    td = O.divdiv_tau(cfg, uU, 0.05)
+    ref = np.linalg.norm(U) * np.cbrt(vol) * 0.05
+    assert np.abs(td - ref).max() <= 1e-13 * ref.max()
+    rng = np.random.default_rng(6)
+    tau_d = rng.uniform(0.5, 2.0, cfg.ncell)
+    u, v = rng.uniform(-1, 1, cfg.n_vel), rng.uniform(-1, 1, cfg.n_vel)
+    du, dv = O.divdiv_apply(cfg, u, tau_d), O.divdiv_apply(cfg, v, tau_d)
+    assert abs(v @ du - u @ dv) <= 1e-12 * (np.abs(v) @ np.abs(du))
+    assert np.abs(O.divdiv_apply(cfg, uU, tau_d)).max() <= 1e-13 * np.abs(du).max()
+    dY = O.divdiv_apply(cfg, uY, tau_d)
+    en = (uY[:cfg.ncell * 3 * n3] * dY[:cfg.ncell * 3 * n3]).reshape(cfg.ncell, -1).sum(1)
+    assert np.abs(en - tau_d * vol).max() <= 1e-12 * (tau_d * vol).max()
 
 
 def test_enrichment_rows_with_linear_psi():
@@ -172,6 +217,20 @@ def test_enrichment_rows_with_linear_psi():
             worst = max(worst, abs(g[off + 3 * k + c] - ref) / (np.abs(ps) @ np.abs(rows)))
             up[e, c] += ut[3 * k + c] * ps
     assert worst <= 1e-12
-    c_enr = O.velocity_divergence(cfg, np.concatenate([ubar, ut]), tau=tau)
-    c_pol = O.velocity_divergence(cfg, np.concatenate([up.ravel(), np.zeros(3 * len(cells))]), tau=tau)
+    u_enr, u_pol = np.concatenate([ubar, ut]), np.concatenate([up.ravel(), np.zeros(3 * len(cells))])
+    c_enr = O.velocity_divergence(cfg, u_enr, tau=tau)
+    c_pol = O.velocity_divergence(cfg, u_pol, tau=tau)
     assert np.abs(c_enr - c_pol).max() <= 1e-12 * np.abs(c_pol).max()
+    # the div-div penalty and tau_D: the same field gives the same values, the
+    # enrichment rows are the polynomial rows weighted by psi at the nodes
+    t_enr, t_pol = O.divdiv_tau(cfg, u_enr, 0.05, tau=tau), O.divdiv_tau(cfg, u_pol, 0.05, tau=tau)
+    assert np.abs(t_enr - t_pol).max() <= 1e-12 * np.abs(t_pol).max()
+    tau_d = rng.uniform(0.5, 2.0, cfg.ncell)
+    d_enr, d_pol = O.divdiv_apply(cfg, u_enr, tau_d, tau=tau), O.divdiv_apply(cfg, u_pol, tau_d, tau=tau)
+    assert np.abs(d_enr[:off] - d_pol[:off]).max() <= 1e-12 * np.abs(d_pol[:off]).max()
+    for k, e in enumerate(cells):
+        ps = np.array([O.psi_point(cfg, tau, int(e), (gl[B % n], gl[(B // n) % n], gl[B // (n * n)]))[0]
+                       for B in range(n3)])
+        for c in range(3):
+            rows = d_pol[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
+            assert abs(d_enr[off + 3 * k + c] - ps @ rows) <= 1e-12 * (np.abs(ps) @ np.abs(rows))
