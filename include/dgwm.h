@@ -320,7 +320,8 @@ int dg_apply_velocity_divergence(const dg_mesh* mesh, const double* u, double* c
  * cell's velocity rule), h_e the cube root of the cell volume and dt_over_cr
  * the time step over the global Courant number.
  *   u: device, dg_num_dofs(mesh, 0) doubles (the previous step's velocity);
- *   tau_d: device output, nx*ny*nz doubles in cell order.  Flat meshes only.
+ *   tau_d: device output, nx*ny*nz doubles in cell order.  Curved-wall
+ *   meshes (l = 0) take J^{-1} and |det J| per point.
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
 int dg_divdiv_tau(const dg_mesh* mesh, const double* u, double dt_over_cr, double* tau_d, void* stream);
 
@@ -329,7 +330,8 @@ int dg_divdiv_tau(const dg_mesh* mesh, const double* u, double dt_over_cr, doubl
  * psi e_c (l = 0) or psi N_B e_c (l = 1) in enriched cells), u the full
  * velocity, with the cell's velocity rule; cell-local.
  *   tau_d: device, nx*ny*nz doubles (e.g. from dg_divdiv_tau); u, out:
- *   device, dg_num_dofs(mesh, 0) doubles, distinct.  Flat meshes only.
+ *   device, dg_num_dofs(mesh, 0) doubles, distinct.  Curved-wall meshes
+ *   (l = 0) take J^{-1} and |det J| per point.
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
 int dg_apply_divdiv(const dg_mesh* mesh, const double* tau_d, const double* u, double* out, void* stream);
 

@@ -453,7 +453,6 @@ int dg_apply_velocity_divergence(const dg_mesh* m, const double* u, double* c, v
 
 int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* tau_d, void* stream) {
   if (!m || !u || !tau_d) return set_error(DG_ERR_ARG, "mesh/u/tau_d is NULL");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
   if (!(dt_over_cr >= 0) || !std::isfinite(dt_over_cr)) return set_error(DG_ERR_ARG, "dt/Cr must be >= 0 and finite");
   if (static_cast<const void*>(u) == static_cast<const void*>(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must not alias");
   if (!aligned256(u) || !aligned256(tau_d)) return set_error(DG_ERR_ARG, "u and tau_d must be 256-byte aligned");
@@ -462,7 +461,6 @@ int dg_divdiv_tau(const dg_mesh* m, const double* u, double dt_over_cr, double* 
 
 int dg_apply_divdiv(const dg_mesh* m, const double* tau_d, const double* u, double* out, void* stream) {
   if (!m || !tau_d || !u || !out) return set_error(DG_ERR_ARG, "mesh/tau_d/u/out is NULL");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "div-div penalty: flat meshes only");
   if (u == out) return set_error(DG_ERR_ARG, "u and out must not alias");
   if (!aligned256(u) || !aligned256(out) || !aligned256(tau_d))
     return set_error(DG_ERR_ARG, "tau_d, u and out must be 256-byte aligned");

@@ -233,6 +233,8 @@ int launch_viscous_multiscale(const dg_mesh* m, const double* nut, const double*
 // div-div penalty: tau_D per cell from u (tau = true, out: ncell doubles) or out = D u with tau_d
 int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr, double* out,
                   hipStream_t s);
+int launch_divdiv_curved(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr,
+                         double* out, hipStream_t s);
 // out = C u (divergence, pressure layout) or P p (gradient, velocity layout), flat meshes
 int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s);
 int launch_divgrad_curved(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s);

@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kDdThreads) void divdiv_apply_kernel(const DdArgs A
 
 int launch_divdiv(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr, double* out,
                   hipStream_t s) {
+  if (m->curved) return launch_divdiv_curved(m, tau, u, tau_d, dt_over_cr, out, s);
   DdArgs A;
   A.nx = m->P.nx;
   A.ny = m->P.ny;

@@ -1,5 +1,6 @@
 // Pressure gradient and velocity divergence terms of the dual-splitting
-// scheme (arXiv 1705.08813, Sec. 4.2) on the curved-wall mesh, FP64:
+// scheme (arXiv 1705.08813, Sec. 4.2) and the div-div penalty of its
+// projection step on the curved-wall mesh, FP64:
 //
 //   P: g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}     (velocity test functions)
 //   C: c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}    (pressure test functions)
@@ -364,7 +365,167 @@ __global__ __launch_bounds__(kCvThreads) void curved_divergence_kernel(const CvA
   for (int B = tid; B < NP3; B += kCvThreads) A.out[c.e * NP3 + B] = acc[B];
 }
 
+// ---------------------------------------------------------------------------
+// Div-div penalty of the projection step (Sec. 4.2, eqs. div-div and tauD),
+// cell-local: TAU computes tau_D,e = (int_e |u| / |e|) |e|^(1/3) dt/Cr (u the
+// full velocity); otherwise out = D u with
+//   D u (v) = tau_D,e (div u, div v)_e,  div u = sum_c sum_a J^{-1}[a][c] d_a u_c (+ grad psi . u~),
+// and the test-function integrals sum_q sum_a d_a N_B(q) J^{-1}[a][c] f(q), f = w|J| tau_D div u.
+template <int NPU, int NQ, int NQY, bool ENR, bool TAU>
+__global__ __launch_bounds__(kCvThreads) void curved_divdiv_kernel(const CvArgs A, const double* tau_d,
+                                                                   double dt_over_cr, int layer_lo, int nlayers) {
+  constexpr int QY = ENR ? NQY : NQ;
+  constexpr int NU3 = NPU * NPU * NPU, NPT = NQ * QY * NQ;
+  constexpr auto& ux = ct::tab<NPU, NQ>;
+  constexpr auto& uy = ct::tab<NPU, QY>;
+  __shared__ double su[3 * NU3];
+  __shared__ double F[TAU ? 1 : 9][TAU ? 1 : NPT];
+  __shared__ double red[3 * (kCvThreads / 64)];
+  __shared__ double sut[3];
+  const int tid = threadIdx.x;
+  const CvCell c = cv_cell<ENR>(A, blockIdx.x, layer_lo, nlayers);
+  for (int k = tid; k < 3 * NU3; k += kCvThreads) su[k] = A.in[c.e * 3 * NU3 + k];
+  if (tid < 3) sut[tid] = ENR ? A.in[A.ncell * 3 * NU3 + c.enr * 3 + tid] : 0.0;
+  __syncthreads();
+  const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
+  const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
+  if constexpr (TAU) {
+    double v[2] = {0.0, 0.0};  // int |u|, |e|
+    for (int q = tid; q < NPT; q += kCvThreads) {
+      const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
+      double u[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < NPU; ++k)
+        for (int j = 0; j < NPU; ++j) {
+          const double fy = uy.S[qy][j] * ux.S[qz][k];
+          for (int i = 0; i < NPU; ++i) {
+            const double b = ux.S[qx][i] * fy;
+            const int B = i + NPU * (j + NPU * k);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) u[d] += b * su[d * NU3 + B];
+          }
+        }
+      if (ENR)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] += ps[q * 4] * sut[d];
+      const double w = geo[q * 10 + 9];
+      v[0] += w * sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      v[1] += w;
+    }
+    cv_block_sum<2>(v, red, tid);
+    if (tid == 0) A.out[c.e] = v[0] / v[1] * cbrt(v[1]) * dt_over_cr;
+  } else {
+    const double td = tau_d[c.e];
+    double ev[3] = {0.0, 0.0, 0.0};
+    for (int q = tid; q < NPT; q += kCvThreads) {
+      const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
+      double du[3][3] = {};  // [c][a] = d u_c / d xi_a
+      for (int k = 0; k < NPU; ++k)
+        for (int j = 0; j < NPU; ++j) {
+          const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
+          const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
+          for (int i = 0; i < NPU; ++i) {
+            const double b0 = ux.Sd[qx][i] * yz, b1 = ux.S[qx][i] * dyz, b2 = ux.S[qx][i] * ydz;
+            const int B = i + NPU * (j + NPU * k);
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+              const double uv = su[cc * NU3 + B];
+              du[cc][0] += b0 * uv;
+              du[cc][1] += b1 * uv;
+              du[cc][2] += b2 * uv;
+            }
+          }
+        }
+      const double* g = geo + q * 10;
+      double div = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) div += g[3 * a + cc] * du[cc][a];
+      if (ENR)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) div += ps[q * 4 + 1 + cc] * sut[cc];
+      const double f = g[9] * td * div;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) F[a][q] = g[a] * f;  // F[3a + c] = J^{-1}[a][c] f
+      if (ENR)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) ev[cc] += ps[q * 4 + 1 + cc] * f;
+    }
+    __syncthreads();
+    double* o = A.out + c.e * 3 * NU3;
+    for (int it = tid; it < 3 * NU3; it += kCvThreads) {
+      const int cc = it / NU3, B = it - cc * NU3;
+      const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
+      double s = 0.0;
+      for (int qz = 0; qz < NQ; ++qz)
+        for (int qy = 0; qy < QY; ++qy) {
+          const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
+          const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
+          for (int qx = 0; qx < NQ; ++qx) {
+            const int q = qx + NQ * (qy + QY * qz);
+            s += ux.Sd[qx][i] * yz * F[cc][q] + ux.S[qx][i] * dyz * F[3 + cc][q] + ux.S[qx][i] * ydz * F[6 + cc][q];
+          }
+        }
+      o[it] = s;
+    }
+    if (ENR) {
+      cv_block_sum<3>(ev, red, tid);
+      if (tid < 3) A.out[A.ncell * 3 * NU3 + c.enr * 3 + tid] = ev[tid];
+    }
+  }
+}
+
 }  // namespace
+
+// (k_u+1, nq_u, nq_wn) combinations of the velocity operators
+#define DG_CVD_COMBOS(X) X(3, 4, 8) X(3, 4, 4) X(4, 4, 8) X(4, 5, 8) X(4, 5, 5) X(5, 7, 8) X(6, 8, 8)
+
+int launch_divdiv_curved(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr,
+                         double* out, hipStream_t s) {
+  CvArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.upper_slot = m->upper_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  A.geo_stride = m->geo_stride;
+  A.fully_periodic = m->P.fully_periodic;
+  A.ncell = m->ncell;
+  A.geo = m->geo;
+  A.psi = m->psi;
+  A.in = u;
+  A.out = out;
+  if (!m->geo || m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "curved div-div: l = 0 enrichment only");
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
+  const bool any_w = m->nenr == 0;
+  const int nqw = m->P.nq_wn;
+#define LAUNCH(p, q, w, ENRV, TAUV, grid, lo_, nl_)                                                       \
+  hipLaunchKernelGGL((curved_divdiv_kernel<p, q, w, ENRV, TAUV>), dim3((unsigned)(grid)), dim3(kCvThreads), 0, s, \
+                     A, tau_d, dt_over_cr, lo_, nl_)
+#define X(p, q, w)                                                                                      \
+  if (m->np_u == p && m->P.nq_u == q && (any_w || nqw == w)) {                                          \
+    if (nreg > 0) {                                                                                     \
+      if (tau) LAUNCH(p, q, w, false, true, nreg, lo, nl);                                              \
+      else LAUNCH(p, q, w, false, false, nreg, lo, nl);                                                 \
+      const int rc = check_hip(hipGetLastError(), "curved div-div kernel launch");                      \
+      if (rc) return rc;                                                                                \
+    }                                                                                                   \
+    if (m->nenr > 0) {                                                                                  \
+      if (tau) LAUNCH(p, q, w, true, true, m->nenr, 0, 0);                                              \
+      else LAUNCH(p, q, w, true, false, m->nenr, 0, 0);                                                 \
+    }                                                                                                   \
+    return check_hip(hipGetLastError(), "curved div-div kernel launch");                                \
+  }
+  DG_CVD_COMBOS(X)
+#undef X
+#undef LAUNCH
+  return set_error(DG_ERR_UNSUPPORTED, "curved div-div penalty: (k_u+1, nq_u, nq_wn) combination not compiled");
+}
 
 // (k_u+1, k_p+1, nq_u, nq_wn) combinations: the velocity ones with k_p = k_u - 1
 #define DG_CV_COMBOS(X) X(3, 2, 4, 8) X(3, 2, 4, 4) X(4, 3, 4, 8) X(4, 3, 5, 8) X(4, 3, 5, 5) X(5, 4, 7, 8) X(6, 5, 8, 8)

@@ -83,12 +83,69 @@ def test_divdiv_large_mesh_sampled():
     assert _rel(d[erows], do[erows]) <= TOL
 
 
+# The curved-wall mesh (Sec. 5.2 geometry; per-point J^{-1} and |det J| of the isoparametric cells).
+CURVED = {
+    "curved_k3": MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3),
+    "curved_k5": MeshConfig(nx=3, ny=3, nz=2, wall_amp=0.3, gamma=1.2, k_u=5, nq_u=8, nq_wn=8, k_p=4, nq_p=5),
+    "curved_k4_two_layers": MeshConfig(nx=3, ny=2, nz=2, wall_amp=0.25, k_u=4, nq_u=7, nq_wn=8, k_p=3, nq_p=4),
+    "curved_k2_plain": MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=2, nq_u=4, nq_wn=4, k_p=1, nq_p=2,
+                                  enrich_lower=0, enrich_upper=0),
+    "curved_k3_lower_only": MeshConfig(nx=3, ny=3, nz=2, wall_amp=0.3, gamma=0.8, k_u=3, nq_u=5, nq_wn=8, k_p=2,
+                                       nq_p=3, enrich_upper=0),
+}
+
+
+@pytest.mark.parametrize("name", list(CURVED))
+def test_curved_divdiv_matches_oracle(name):
+    cfg = CURVED[name]
+    print(f"[gpu] curved div-div case={name}", flush=True)
+    inp = draw_inputs(Workload("ddc", cfg, 33, 0.2, 2.0))
+    u_prev = np.random.default_rng(34).uniform(-1, 1, cfg.n_vel)
+    mesh = Mesh(cfg, inp["tau"])
+    td = mesh.divdiv_tau(torch.tensor(u_prev, device="cuda"), 0.37).cpu().numpy()
+    tdo = O.divdiv_tau(cfg, u_prev, 0.37, tau=inp["tau"])
+    d = mesh.apply_divdiv(torch.tensor(tdo, device="cuda"), torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    do = O.divdiv_apply(cfg, inp["u"], tdo, tau=inp["tau"])
+    n = cfg.ncell * 3 * (cfg.k_u + 1) ** 3
+    print(f"[gpu]   tau {_rel(td, tdo):.2e} poly {_rel(d[:n], do[:n]):.2e} "
+          f"enr {_rel(d[n:], do[n:]) if n < d.size else 0:.2e}", flush=True)
+    assert _rel(td, tdo) <= TOL
+    assert _rel(d[:n], do[:n]) <= TOL
+    if n < d.size:
+        assert _rel(d[n:], do[n:]) <= TOL
+
+
+def test_curved_divdiv_workload_sampled():
+    """The 48 x 24 x 24, k = 5 curved workload on sampled cells (wall rows included)."""
+    wl = PRESETS["curved"]
+    cfg = wl.mesh
+    print("[gpu] curved div-div 48x24x24", flush=True)
+    inp = draw_inputs(wl)
+    mesh = Mesh(cfg, inp["tau"])
+    u = torch.tensor(inp["u"], device="cuda")
+    td = mesh.divdiv_tau(u, 0.05).cpu().numpy()
+    rng = np.random.default_rng(10)
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    cells = set(rng.integers(0, cfg.ncell, 16).tolist())
+    for ey in (0, 1, ny - 2, ny - 1):
+        for _ in range(4):
+            cells.add(int(rng.integers(0, nx)) + nx * (ey + ny * int(rng.integers(0, nz))))
+    cells = np.array(sorted(cells), dtype=np.int64)
+    tdo = O.divdiv_tau(cfg, inp["u"], 0.05, tau=inp["tau"], cells=cells)
+    d = mesh.apply_divdiv(torch.tensor(td, device="cuda"), u).cpu().numpy()
+    do = O.divdiv_apply(cfg, inp["u"], td, tau=inp["tau"], cells=cells)
+    n3 = 3 * (cfg.k_u + 1) ** 3
+    rows = (cells[:, None] * n3 + np.arange(n3)[None, :]).ravel()
+    cl = O.enriched_cells(cfg).tolist()
+    erows = np.array([cfg.ncell * n3 + 3 * cl.index(int(e)) + cc for e in cells if int(e) in cl for cc in range(3)])
+    print(f"[gpu]   {len(cells)} cells: tau {_rel(td[cells], tdo[cells]):.2e} poly {_rel(d[rows], do[rows]):.2e} "
+          f"enr {_rel(d[erows], do[erows]):.2e}", flush=True)
+    assert _rel(td[cells], tdo[cells]) <= TOL
+    assert _rel(d[rows], do[rows]) <= TOL
+    assert erows.size > 0 and _rel(d[erows], do[erows]) <= TOL
+
+
 def test_divdiv_rejects_bad_arguments():
-    mesh = Mesh(MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3))
-    u = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
-    with pytest.raises(DgError) as ei:
-        mesh.divdiv_tau(u, 0.1)
-    assert ei.value.code == -6
     flat = Mesh(CASES["tiny"])
     uf = torch.zeros(flat.n_vel, dtype=torch.float64, device="cuda")
     with pytest.raises(DgError) as ei:
