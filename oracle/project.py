@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import enriched_cells, gauss, gauss_lobatto, lagrange, vertex_eta
+from . import cell_map, enriched_cells, gauss, gauss_lobatto, lagrange, vertex_eta
 
 
 def volume_rule(cfg):
@@ -140,11 +140,12 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     switched off, its unknowns set to 0).  cells: the cells to invert (the
     operator is block diagonal; the others are left at 0).  With return_cond,
     also the 2-norm condition number of each cell's block (0 for cells not
-    inverted).  Flat (box) meshes only.  With degree-1 enrichment weights
+    inverted).  On the curved-wall mesh (l = 0) |det J| enters per point.
+    With degree-1 enrichment weights
     (Sec. 3.1 eq. enrichment, l = 1) the enrichment functions of a cell are
     psi N_B, N_B its eight trilinear vertex functions."""
-    if cfg.wall_amp != 0.0:
-        raise ValueError("flat meshes only")
+    if cfg.wall_amp != 0.0 and _nle(cfg) != 1:
+        raise ValueError("curved meshes: l = 0 only")
     n3 = (cfg.k_u + 1) ** 3
     r = np.asarray(r, dtype=np.float64)
     x = np.zeros_like(r)
@@ -160,7 +161,7 @@ def inverse_mass(cfg, r, psi, cells=None, return_cond=False):
     nle = _nle(cfg)
     for e in (range(cfg.ncell) if cells is None else [int(c) for c in cells]):
         k = enr.get(e)
-        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e, pts_e)
+        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e, pts_e, (pts_r, wts_r, V_r))
         conds[e] = np.linalg.cond(M)
         for c in range(3):
             rp = r[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
@@ -178,8 +179,8 @@ def mass_apply(cfg, x, psi):
     """y = M x with the velocity mass matrix of every cell (the forward
     operator that inverse_mass inverts; same blocks, same psi convention:
     zero rows switch a cell's enrichment off, its unknowns then map to 0)."""
-    if cfg.wall_amp != 0.0:
-        raise ValueError("flat meshes only")
+    if cfg.wall_amp != 0.0 and _nle(cfg) != 1:
+        raise ValueError("curved meshes: l = 0 only")
     n3 = (cfg.k_u + 1) ** 3
     x = np.asarray(x, dtype=np.float64)
     y = np.zeros_like(x)
@@ -194,7 +195,7 @@ def mass_apply(cfg, x, psi):
     nle = _nle(cfg)
     for e in range(cfg.ncell):
         k = enr.get(e)
-        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e, pts_e)
+        M = _mass_block(cfg, e, None if k is None else psi[k], eta, M_reg, V_e, wts_e, pts_e, (pts_r, wts_r, V_r))
         for c in range(3):
             xp = x[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
             if k is not None and M.shape[0] == n3 + nle:
@@ -237,10 +238,26 @@ def _vertex_fns(pts):
     return N
 
 
-def _mass_block(cfg, e, psi_k, eta, M_reg, V_e, wts_e, pts_e=None):
+def _curved_detj(cfg, e, pts):
+    """|det J| at the reference points pts of cell e of the curved-wall mesh
+    (its degree-k_u isoparametric map, Sec. 5.2 geometry)."""
+    return np.abs(np.array([cell_map(cfg, e, p)[1] for p in pts]))
+
+
+def _mass_block(cfg, e, psi_k, eta, M_reg, V_e, wts_e, pts_e=None, reg=None):
     """Per-component mass matrix of cell e over its local basis (N_B, plus the
     enrichment functions psi N^l_B while an enriched cell's enrichment is on),
-    the cell's own rule."""
+    the cell's own rule.  On the curved-wall mesh |det J| varies over the cell
+    and enters point by point (reg: points, weights and basis values of the
+    regular rule, for the cells without enrichment)."""
+    if cfg.wall_amp != 0.0:
+        pts, wts, V = reg if psi_k is None else (pts_e, wts_e, V_e)
+        w = wts * _curved_detj(cfg, e, pts)
+        if psi_k is None:
+            return V.T @ (w[:, None] * V)
+        ps = np.asarray(psi_k, dtype=float)
+        Phi = np.hstack([V, ps[:, None]]) if np.any(ps != 0.0) else V
+        return Phi.T @ (w[:, None] * Phi)
     hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
     ey = (e // cfg.nx) % cfg.ny
     detJ = hx * (eta[ey + 1] - eta[ey]) * hz
@@ -266,7 +283,7 @@ def mass_block(cfg, e, psi_k=None):
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
     V_r = basis_at(cfg, pts_r)
     M_reg = V_r.T @ (wts_r[:, None] * V_r)
-    return _mass_block(cfg, int(e), psi_k, vertex_eta(cfg), M_reg, V_e, wts_e, pts_e)
+    return _mass_block(cfg, int(e), psi_k, vertex_eta(cfg), M_reg, V_e, wts_e, pts_e, (pts_r, wts_r, V_r))
 
 
 def _basis_grad_at(cfg, pts, h):

@@ -234,3 +234,71 @@ def test_enrichment_rows_with_linear_psi():
         for c in range(3):
             rows = d_pol[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
             assert abs(d_enr[off + 3 * k + c] - ps @ rows) <= 1e-12 * (np.abs(ps) @ np.abs(rows))
+
+
+def _numpy_mass(cfg, e, Y, nqx, nqy, psi_k=None):
+    """Mass matrix of curved cell e from the map's definition in numpy:
+    hx hz sum_q w_q dy/dxi_y(q) phi_i(q) phi_j(q) over an nqx x nqy x nqx Gauss
+    rule (phi: the nodal basis, plus psi_k given at that rule's points)."""
+    n = cfg.k_u + 1
+    gl = _gl_nodes(n)
+    gx, wx = np.polynomial.legendre.leggauss(nqx)
+    gy, wy = np.polynomial.legendre.leggauss(nqy)
+    gx, wx, gy, wy = 0.5 * (gx + 1), 0.5 * wx, 0.5 * (gy + 1), 0.5 * wy
+    vx, dx = _lagrange(gl, gx)
+    vy, dy = _lagrange(gl, gy)
+    dydy = np.einsum("ai,bj,ij->ab", vx, dy, Y[e])                       # [qx][qy]
+    w = cfg.Lx / cfg.nx * cfg.Lz / cfg.nz * np.einsum("a,b,c,ab->cba", wx, wy, wx, dydy).ravel()
+    V = np.einsum("ai,bj,ck->cbakji", vx, vy, vx).reshape(nqx * nqy * nqx, n ** 3)   # q = qx + nqx (qy + nqy qz)
+    Phi = V if psi_k is None else np.hstack([V, np.asarray(psi_k)[:, None]])
+    return Phi.T @ (w[:, None] * Phi)
+
+
+@pytest.mark.parametrize("name", list(CURVED))
+def test_mass_matrix_on_curved_cells(name):
+    """The velocity mass matrix (M du/dt = -R(u), Sec. 4.1) of a curved cell
+    against the numpy matrix with |det J| from the map's definition (the
+    cell's rule integrates its polynomial integrand exactly), and M^{-1}."""
+    from oracle import project as OP
+    cfg = CURVED[name]
+    n3 = (cfg.k_u + 1) ** 3
+    _, Y = _mapped_y(cfg)
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, cfg.n_vel)
+    y = OP.mass_apply(cfg, x, [])
+    for e in range(cfg.ncell):
+        M = _numpy_mass(cfg, e, Y, 2 * cfg.k_u + 2, 2 * cfg.k_u + 2)
+        for c in range(3):
+            blk = slice((e * 3 + c) * n3, (e * 3 + c + 1) * n3)
+            ref = M @ x[blk]
+            assert np.abs(y[blk] - ref).max() <= 1e-13 * np.abs(M).sum(1).max() * np.abs(x[blk]).max()
+    xi = OP.inverse_mass(cfg, y, [])
+    assert np.abs(xi - x).max() <= 1e-10
+
+
+def test_mass_matrix_on_curved_enriched_cells():
+    """Enriched curved cells: the bordered block (psi row and column) against
+    numpy with the oracle's psi at the enriched rule, and M^{-1} M = I within
+    eps cond(M)."""
+    from oracle import project as OP
+    cfg = MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3)
+    n3 = (cfg.k_u + 1) ** 3
+    rng = np.random.default_rng(8)
+    tau = rng.uniform(0.2, 2.0, cfg.n_tau)
+    cells = O.enriched_cells(cfg)
+    psi = O.psi_volume(cfg, cells, tau=tau)
+    _, Y = _mapped_y(cfg)
+    x = rng.uniform(-1, 1, cfg.n_vel)
+    y = OP.mass_apply(cfg, x, psi)
+    off = cfg.ncell * 3 * n3
+    for k, e in enumerate(cells):
+        M = _numpy_mass(cfg, int(e), Y, cfg.nq_u, cfg.nq_wn, psi[k])
+        for c in range(3):
+            blk = slice((int(e) * 3 + c) * n3, (int(e) * 3 + c + 1) * n3)
+            xe = np.concatenate([x[blk], [x[off + 3 * k + c]]])
+            ref = M @ xe
+            scale = np.abs(M).sum(1).max() * np.abs(xe).max()
+            assert np.abs(y[blk] - ref[:n3]).max() <= 1e-13 * scale
+            assert abs(y[off + 3 * k + c] - ref[n3]) <= 1e-13 * scale
+    xi, cond = OP.inverse_mass(cfg, y, psi, return_cond=True)
+    assert np.abs(xi - x).max() <= 64 * 2.0 ** -52 * cond.max() * np.abs(x).max()
