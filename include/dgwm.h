@@ -280,9 +280,15 @@ int dg_apply_velocity_residual_batched(const dg_mesh* const* meshes, int32_t n, 
  * accuracy of any M^{-1} r there.  The first call after setup or after a
  * wall-shear update also fills a per-mesh cache of the enriched cells'
  * polynomial parts of psi on `stream`; a later call on another stream must be
- * ordered after that one.
+ * ordered after that one.  On the curved-wall mesh (l = 0) a cell's block has
+ * no tensor-product inverse (|det J| varies over the cell): each cell runs
+ * preconditioned CG on its polynomial block (the tensor inverse of the
+ * reference mass matrix over the cell volume as preconditioner, at most 100
+ * iterations, to a relative residual of 1e-15), and an enriched cell
+ * eliminates its psi row through the Schur complement formed pointwise.
  *   r, x: device, dg_num_dofs(mesh, 0) doubles; x may be r (in place).
- *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (curved lower wall), DG_ERR_HIP. */
+ *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED (a degree combination not
+ *   compiled), DG_ERR_HIP. */
 int dg_apply_inverse_mass(const dg_mesh* mesh, const double* r, double* x, void* stream);
 
 /* Pressure gradient term of the dual-splitting scheme (paper Sec. 4.2):

@@ -432,7 +432,6 @@ int dg_project_velocity(const dg_mesh* m, const double* u_old, double* u_new, vo
 
 int dg_apply_inverse_mass(const dg_mesh* m, const double* r, double* x, void* stream) {
   if (!m || !r || !x) return set_error(DG_ERR_ARG, "mesh/r/x is NULL");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "inverse mass: flat meshes only");
   if (!aligned256(r) || !aligned256(x)) return set_error(DG_ERR_ARG, "r and x must be 256-byte aligned");
   return launch_inverse_mass(m, r, x, static_cast<hipStream_t>(stream));
 }

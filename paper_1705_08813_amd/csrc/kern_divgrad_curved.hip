@@ -1,6 +1,7 @@
 // Pressure gradient and velocity divergence terms of the dual-splitting
-// scheme (arXiv 1705.08813, Sec. 4.2) and the div-div penalty of its
-// projection step on the curved-wall mesh, FP64:
+// scheme (arXiv 1705.08813, Sec. 4.2), the div-div penalty of its
+// projection step and the inverse velocity mass matrix on the curved-wall
+// mesh, FP64:
 //
 //   P: g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}     (velocity test functions)
 //   C: c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}    (pressure test functions)
@@ -475,10 +476,278 @@ __global__ __launch_bounds__(kCvThreads) void curved_divdiv_kernel(const CvArgs 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Inverse velocity mass matrix on the curved-wall mesh, x = M^{-1} r per cell
+// and component.  A curved cell's polynomial block A_BB' = sum_q W(q) N_B N_B'
+// (W = w |det J|) has no tensor-product inverse, so it is solved by
+// preconditioned CG, all right-hand sides of the cell at once, with the
+// tensor inverse of the reference mass matrix scaled by the cell volume,
+// K^{-1} / |e|, as the preconditioner (|det J| varies mildly over a cell, so
+// a few tens of iterations reach the rounding floor).  An enriched cell adds
+// a = A^{-1} (N, psi)_W as a fourth right-hand side and eliminates its psi
+// row through the Schur complement s = (psi - sum_B a_B N_B, same)_W, formed
+// pointwise as on flat cells:
+//   x_psi = (r_psi - (N psi)_W . y) / s,  x_poly = y - a x_psi,  y = A^{-1} r_poly,
+// x_psi = 0 while the cell's enrichment is switched off.  The cell's inputs
+// are read before any output is written, so x may be r.
+constexpr int kCvMaxIt = 100;
+constexpr double kCvTol = 1e-15;
+
+template <int NPU, int NQ, int QY, int NV>
+__device__ __forceinline__ void cv_mass_apply(const double (*P)[NPU * NPU * NPU], double (*Y)[NPU * NPU * NPU],
+                                              double (*T)[NQ * QY * NQ], const double* W, int tid) {
+  constexpr int NU3 = NPU * NPU * NPU, NPT = NQ * QY * NQ;
+  constexpr auto& ux = ct::tab<NPU, NQ>;
+  constexpr auto& uy = ct::tab<NPU, QY>;
+  for (int q = tid; q < NPT; q += kCvThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
+    double v[NV] = {};
+    for (int k = 0; k < NPU; ++k)
+      for (int j = 0; j < NPU; ++j) {
+        const double fy = uy.S[qy][j] * ux.S[qz][k];
+        for (int i = 0; i < NPU; ++i) {
+          const double b = ux.S[qx][i] * fy;
+          const int B = i + NPU * (j + NPU * k);
+#pragma unroll
+          for (int r = 0; r < NV; ++r) v[r] += b * P[r][B];
+        }
+      }
+#pragma unroll
+    for (int r = 0; r < NV; ++r) T[r][q] = W[q] * v[r];
+  }
+  __syncthreads();
+  for (int it = tid; it < NV * NU3; it += kCvThreads) {
+    const int r = it / NU3, B = it - r * NU3;
+    const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
+    double s = 0.0;
+    for (int qz = 0; qz < NQ; ++qz)
+      for (int qy = 0; qy < QY; ++qy) {
+        const double yz = uy.S[qy][j] * ux.S[qz][k];
+        for (int qx = 0; qx < NQ; ++qx) s += ux.S[qx][i] * yz * T[r][qx + NQ * (qy + QY * qz)];
+      }
+    Y[r][B] = s;
+  }
+  __syncthreads();
+}
+
+// z = (K^{-1} r) / vol with K^{-1} = Mi (x) Mi (x) Mi; t1, t2: scratch of NV * NU3.
+template <int NPU, int NV>
+__device__ __forceinline__ void cv_precond(const double (*R)[NPU * NPU * NPU], double (*Z)[NPU * NPU * NPU],
+                                           double* t1, double* t2, const double* Mi, double vol, int tid) {
+  constexpr int NU3 = NPU * NPU * NPU;
+  for (int it = tid; it < NV * NU3; it += kCvThreads) {
+    const int r = it / NU3, B = it - r * NU3, i = B % NPU, rest = B - i;
+    double s = 0.0;
+    for (int a = 0; a < NPU; ++a) s += Mi[i * NPU + a] * R[r][rest + a];
+    t1[it] = s;
+  }
+  __syncthreads();
+  for (int it = tid; it < NV * NU3; it += kCvThreads) {
+    const int r = it / NU3, B = it - r * NU3, j = (B / NPU) % NPU, rest = B - j * NPU;
+    double s = 0.0;
+    for (int a = 0; a < NPU; ++a) s += Mi[j * NPU + a] * t1[r * NU3 + rest + a * NPU];
+    t2[it] = s;
+  }
+  __syncthreads();
+  for (int it = tid; it < NV * NU3; it += kCvThreads) {
+    const int r = it / NU3, B = it - r * NU3, k = B / (NPU * NPU), rest = B - k * NPU * NPU;
+    double s = 0.0;
+    for (int a = 0; a < NPU; ++a) s += Mi[k * NPU + a] * t2[r * NU3 + rest + a * NPU * NPU];
+    Z[r][B] = s / vol;
+  }
+  __syncthreads();
+}
+
+template <int NPU, int NQ, int NQY, bool ENR>
+__global__ __launch_bounds__(kCvThreads) void curved_invmass_kernel(const CvArgs A, const double* minv,
+                                                                    const int32_t* act, int layer_lo, int nlayers) {
+  constexpr int QY = ENR ? NQY : NQ;
+  constexpr int NU3 = NPU * NPU * NPU, NPT = NQ * QY * NQ, NV = ENR ? 4 : 3;
+  constexpr auto& ux = ct::tab<NPU, NQ>;
+  constexpr auto& uy = ct::tab<NPU, QY>;
+  __shared__ double X[NV][NU3], R[NV][NU3], Z[NV][NU3], P[NV][NU3], AP[NV][NU3];
+  __shared__ double T[NV][NPT];
+  __shared__ double W[NPT], PS[ENR ? NPT : 1], B0[ENR ? NU3 : 1];
+  __shared__ double Mi[NPU * NPU];
+  __shared__ double red[3 * NV * (kCvThreads / 64)];
+  __shared__ double rhs_e[3];
+  const int tid = threadIdx.x;
+  const CvCell c = cv_cell<ENR>(A, blockIdx.x, layer_lo, nlayers);
+  const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
+  const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
+  const int64_t n_poly = A.ncell * 3 * NU3;
+  for (int k = tid; k < NPU * NPU; k += kCvThreads) Mi[k] = minv[k];
+  for (int k = tid; k < 3 * NU3; k += kCvThreads) R[k / NU3][k % NU3] = A.in[c.e * 3 * NU3 + k];
+  if (ENR && tid < 3) rhs_e[tid] = A.in[n_poly + c.enr * 3 + tid];
+  double vv[1] = {0.0};
+  for (int q = tid; q < NPT; q += kCvThreads) {
+    W[q] = geo[q * 10 + 9];
+    vv[0] += W[q];
+    if (ENR) {
+      PS[q] = ps[q * 4];
+      T[0][q] = W[q] * PS[q];
+    }
+  }
+  cv_block_sum<1>(vv, red, tid);  // (ends with the barrier the loads need)
+  const double vol = vv[0];
+  if (ENR) {
+    // fourth right-hand side (N_B, psi)_W
+    for (int B = tid; B < NU3; B += kCvThreads) {
+      const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
+      double s = 0.0;
+      for (int qz = 0; qz < NQ; ++qz)
+        for (int qy = 0; qy < QY; ++qy) {
+          const double yz = uy.S[qy][j] * ux.S[qz][k];
+          for (int qx = 0; qx < NQ; ++qx) s += ux.S[qx][i] * yz * T[0][qx + NQ * (qy + QY * qz)];
+        }
+      R[3][B] = s;
+      B0[B] = s;
+    }
+    __syncthreads();
+  }
+  // PCG from x = 0 on all NV right-hand sides
+  for (int k = tid; k < NV * NU3; k += kCvThreads) X[k / NU3][k % NU3] = 0.0;
+  cv_precond<NPU, NV>(R, Z, &T[0][0], &AP[0][0], Mi, vol, tid);
+  double rz[NV], bb[NV];
+  {
+    double v[2 * NV] = {};
+    for (int k = tid; k < NV * NU3; k += kCvThreads) {
+      const int r = k / NU3, B = k - r * NU3;
+      v[r] += R[r][B] * Z[r][B];
+      v[NV + r] += R[r][B] * R[r][B];
+      P[r][B] = Z[r][B];
+    }
+    cv_block_sum<2 * NV>(v, red, tid);
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      rz[r] = v[r];
+      bb[r] = v[NV + r];
+    }
+  }
+  bool done[NV];
+#pragma unroll
+  for (int r = 0; r < NV; ++r) done[r] = !(bb[r] > 0.0);
+  for (int it = 0; it < kCvMaxIt; ++it) {
+    bool all = true;
+#pragma unroll
+    for (int r = 0; r < NV; ++r) all = all && done[r];
+    if (all) break;
+    cv_mass_apply<NPU, NQ, QY, NV>(P, AP, T, W, tid);
+    double pa[NV] = {};
+    for (int k = tid; k < NV * NU3; k += kCvThreads) {
+      const int r = k / NU3, B = k - r * NU3;
+      pa[r] += P[r][B] * AP[r][B];
+    }
+    cv_block_sum<NV>(pa, red, tid);
+    double al[NV];
+#pragma unroll
+    for (int r = 0; r < NV; ++r) al[r] = (done[r] || !(pa[r] > 0.0)) ? 0.0 : rz[r] / pa[r];
+    for (int k = tid; k < NV * NU3; k += kCvThreads) {
+      const int r = k / NU3, B = k - r * NU3;
+      X[r][B] += al[r] * P[r][B];
+      R[r][B] -= al[r] * AP[r][B];
+    }
+    __syncthreads();
+    cv_precond<NPU, NV>(R, Z, &T[0][0], &AP[0][0], Mi, vol, tid);
+    double v[2 * NV] = {};
+    for (int k = tid; k < NV * NU3; k += kCvThreads) {
+      const int r = k / NU3, B = k - r * NU3;
+      v[r] += R[r][B] * Z[r][B];
+      v[NV + r] += R[r][B] * R[r][B];
+    }
+    cv_block_sum<2 * NV>(v, red, tid);
+    double be[NV];
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      if (!done[r] && (al[r] == 0.0 || v[NV + r] <= kCvTol * kCvTol * bb[r])) done[r] = true;
+      be[r] = (done[r] || !(rz[r] > 0.0)) ? 0.0 : v[r] / rz[r];
+      if (!done[r]) rz[r] = v[r];
+    }
+    for (int k = tid; k < NV * NU3; k += kCvThreads) {
+      const int r = k / NU3, B = k - r * NU3;
+      if (!done[r]) P[r][B] = Z[r][B] + be[r] * P[r][B];
+    }
+    __syncthreads();
+  }
+  double* o = A.out + c.e * 3 * NU3;
+  if (ENR) {
+    // r_psi = psi - sum_B a_B N_B at the points; s = (r_psi, r_psi)_W; b . y_c
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = tid; q < NPT; q += kCvThreads) {
+      const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
+      double pa = 0.0;
+      for (int k = 0; k < NPU; ++k)
+        for (int j = 0; j < NPU; ++j) {
+          const double fy = uy.S[qy][j] * ux.S[qz][k];
+          for (int i = 0; i < NPU; ++i) pa += ux.S[qx][i] * fy * X[3][i + NPU * (j + NPU * k)];
+        }
+      const double rp = PS[q] - pa;
+      v[0] += W[q] * rp * rp;
+    }
+    for (int B = tid; B < NU3; B += kCvThreads)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) v[1 + cc] += B0[B] * X[cc][B];
+    cv_block_sum<4>(v, red, tid);
+    const bool on = act[c.enr] != 0 && v[0] > 0.0;
+    double xe[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) xe[cc] = on ? (rhs_e[cc] - v[1 + cc]) / v[0] : 0.0;
+    for (int k = tid; k < 3 * NU3; k += kCvThreads) {
+      const int cc = k / NU3, B = k - cc * NU3;
+      o[k] = X[cc][B] - X[3][B] * xe[cc];
+    }
+    if (tid < 3) A.out[n_poly + c.enr * 3 + tid] = xe[tid];
+  } else {
+    for (int k = tid; k < 3 * NU3; k += kCvThreads) o[k] = X[k / NU3][k % NU3];
+  }
+}
+
 }  // namespace
 
 // (k_u+1, nq_u, nq_wn) combinations of the velocity operators
 #define DG_CVD_COMBOS(X) X(3, 4, 8) X(3, 4, 4) X(4, 4, 8) X(4, 5, 8) X(4, 5, 5) X(5, 7, 8) X(6, 8, 8)
+
+int launch_inverse_mass_curved(const dg_mesh* m, const double* r, double* x, hipStream_t s) {
+  CvArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.upper_slot = m->upper_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  A.geo_stride = m->geo_stride;
+  A.fully_periodic = m->P.fully_periodic;
+  A.ncell = m->ncell;
+  A.geo = m->geo;
+  A.psi = m->psi;
+  A.in = r;
+  A.out = x;
+  if (!m->geo || m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "curved inverse mass: l = 0 enrichment only");
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
+  const bool any_w = m->nenr == 0;
+  const int nqw = m->P.nq_wn;
+#define X(p, q, w)                                                                                          \
+  if (m->np_u == p && m->P.nq_u == q && (any_w || nqw == w)) {                                              \
+    if (nreg > 0) {                                                                                         \
+      hipLaunchKernelGGL((curved_invmass_kernel<p, q, w, false>), dim3((unsigned)nreg), dim3(kCvThreads), 0, s, \
+                         A, m->minv, m->act, lo, nl);                                                       \
+      const int rc = check_hip(hipGetLastError(), "curved inverse mass kernel launch");                     \
+      if (rc) return rc;                                                                                    \
+    }                                                                                                       \
+    if (m->nenr > 0)                                                                                        \
+      hipLaunchKernelGGL((curved_invmass_kernel<p, q, w, true>), dim3((unsigned)m->nenr), dim3(kCvThreads), 0, \
+                         s, A, m->minv, m->act, 0, 0);                                                      \
+    return check_hip(hipGetLastError(), "curved inverse mass kernel launch");                               \
+  }
+  DG_CVD_COMBOS(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "curved inverse mass: (k_u+1, nq_u, nq_wn) combination not compiled");
+}
+
 
 int launch_divdiv_curved(const dg_mesh* m, bool tau, const double* u, const double* tau_d, double dt_over_cr,
                          double* out, hipStream_t s) {

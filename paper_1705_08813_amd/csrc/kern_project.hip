@@ -1026,6 +1026,7 @@ int ensure_psi_poly(const dg_mesh* m, const InvMassArgs& A, hipStream_t s) {
 }  // namespace
 
 int launch_inverse_mass(const dg_mesh* m, const double* r, double* x, hipStream_t s) {
+  if (m->curved) return launch_inverse_mass_curved(m, r, x, s);
   const InvMassArgs A = invmass_args(m, r, x);
   const int rc0 = ensure_psi_poly(m, A, s);
   if (rc0) return rc0;

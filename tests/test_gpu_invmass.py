@@ -131,9 +131,80 @@ def test_inverse_mass_large_mesh_sampled():
     _check(cfg, x, ref, conds, cells, inp["u"], psi)
 
 
-def test_inverse_mass_rejects_curved_mesh():
-    mesh = Mesh(MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3))
-    r = torch.zeros(mesh.n_vel, dtype=torch.float64, device="cuda")
-    with pytest.raises(DgError) as ei:
-        mesh.apply_inverse_mass(r)
-    assert ei.value.code == -6
+# The curved-wall mesh (Sec. 5.2 geometry): non-tensor mass blocks, solved by
+# per-cell PCG (and the Schur complement on the psi row in enriched cells).
+# Every cell is held to the forward bound (64 eps cond(M) of its largest entry,
+# at least 1e-12) and to the backward error 2 n eps of its block.
+CURVED = {
+    "curved_k3": MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8, k_p=2, nq_p=3, nu=1.0 / 400),
+    "curved_k5": MeshConfig(nx=3, ny=3, nz=2, wall_amp=0.3, gamma=1.2, k_u=5, nq_u=8, nq_wn=8, k_p=4, nq_p=5),
+    "curved_k4_two_layers": MeshConfig(nx=3, ny=2, nz=2, wall_amp=0.25, k_u=4, nq_u=7, nq_wn=8, k_p=3, nq_p=4),
+    "curved_k2_plain": MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=2, nq_u=4, nq_wn=4, k_p=1, nq_p=2,
+                                  enrich_lower=0, enrich_upper=0),
+    "curved_k3_lower_only": MeshConfig(nx=3, ny=3, nz=2, wall_amp=0.3, gamma=0.8, k_u=3, nq_u=5, nq_wn=8, k_p=2,
+                                       nq_p=3, enrich_upper=0),
+}
+
+
+def _check_curved(cfg, x, r, ref, conds, cells, psi):
+    n1 = (cfg.k_u + 1) ** 3
+    off = cfg.ncell * 3 * n1
+    enr = {int(e): k for k, e in enumerate(O.enriched_cells(cfg))}
+    worst = worst_bwd = 0.0
+    for e in cells:
+        e = int(e)
+        k = enr.get(e)
+        idx = np.arange(e * 3 * n1, (e + 1) * 3 * n1)
+        if k is not None:
+            idx = np.concatenate([idx, off + 3 * k + np.arange(3)])
+        err = np.abs(x[idx] - ref[idx]).max() / max(np.abs(ref[idx]).max(), 1e-300)
+        tol = max(1e-12, 64 * EPS * conds[e])
+        worst = max(worst, err / tol)
+        assert err <= tol, (e, err, tol)
+        M = OP.mass_block(cfg, e, None if k is None else psi[k])
+        for c in range(3):
+            rows = np.arange((e * 3 + c) * n1, (e * 3 + c + 1) * n1)
+            if M.shape[0] == n1 + 1:
+                rows = np.append(rows, off + 3 * k + c)
+            eta = backward_error(M, x[rows], r[rows])
+            worst_bwd = max(worst_bwd, eta / EPS)
+            assert eta <= 2 * M.shape[0] * EPS, (e, c, eta / EPS)
+    _log(f"[gpu]   max cond {conds.max():.2e}, worst err/tol {worst:.3f}, worst backward error {worst_bwd:.1f} eps")
+
+
+@pytest.mark.parametrize("name", list(CURVED))
+def test_curved_inverse_mass_matches_oracle(name):
+    cfg = CURVED[name]
+    _log(f"[gpu] curved inverse mass case={name}")
+    inp = draw_inputs(Workload("imc", cfg, 25, 0.2, 2.0))
+    cells = O.enriched_cells(cfg)
+    psi = O.psi_volume(cfg, cells, tau=inp["tau"]) if cells.size else np.zeros((0, 1))
+    ref, conds = OP.inverse_mass(cfg, inp["u"], psi, return_cond=True)
+    mesh = Mesh(cfg, inp["tau"])
+    r = torch.tensor(inp["u"], device="cuda")
+    xt = mesh.apply_inverse_mass(r)
+    y = r.clone()
+    mesh.apply_inverse_mass(y, y)                       # in place
+    torch.cuda.synchronize()
+    assert torch.equal(xt, y)
+    _check_curved(cfg, xt.cpu().numpy(), inp["u"], ref, conds, range(cfg.ncell), psi)
+
+
+def test_curved_inverse_mass_workload_sampled():
+    """The 48 x 24 x 24, k = 5 curved workload on sampled cells (wall rows included)."""
+    wl = PRESETS["curved"]
+    cfg = wl.mesh
+    _log("[gpu] curved inverse mass 48x24x24")
+    inp = draw_inputs(wl)
+    mesh = Mesh(cfg, inp["tau"])
+    x = mesh.apply_inverse_mass(torch.tensor(inp["u"], device="cuda")).cpu().numpy()
+    rng = np.random.default_rng(26)
+    ecells = O.enriched_cells(cfg)
+    pick_e = np.unique(rng.integers(0, ecells.size, 6))
+    cells = np.unique(np.concatenate([rng.integers(0, cfg.ncell, 10), ecells[pick_e], [0, cfg.ncell - 1]]))
+    psi = np.zeros((ecells.size, cfg.nq_u * cfg.nq_wn * cfg.nq_u))
+    enr = {int(e): k for k, e in enumerate(ecells)}
+    ek = [enr[int(e)] for e in cells if int(e) in enr]
+    psi[ek] = O.psi_volume(cfg, ecells[ek], tau=inp["tau"])
+    ref, conds = OP.inverse_mass(cfg, inp["u"], psi, cells=cells, return_cond=True)
+    _check_curved(cfg, x, inp["u"], ref, conds, cells, psi)
