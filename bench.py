@@ -534,7 +534,7 @@ def main():
         print("bench: curved configuration", file=sys.stderr, flush=True)
         # curved configuration (48x24x24, cosine lower wall, k=5, per-point geometry tables)
         wc = PRESETS["curved"]
-        ic = draw_inputs(wc, want=("u", "tau"))
+        ic = draw_inputs(wc, want=("u", "tau", "p"))
         cmesh = Mesh(wc.mesh, ic["tau"], device=dev)
         cu = torch.tensor(ic["u"], device=dev)
         cr = torch.empty_like(cu)
@@ -560,7 +560,27 @@ def main():
                             "alg_bytes_per_dof_f64": (16.0 * cmesh.n_vel + geo_b) / cmesh.n_vel,
                             "f64_GBps_alg": (16.0 * cmesh.n_vel + geo_b) / times["f64"] / 1e9,
                             "f32_GBps_alg": (8.0 * cmesh.n_vel + geo_b) / times["f32"] / 1e9}
-        del cmesh, cu, cr, cu32, cr32
+        # the pressure-projection terms on the curved cells: P, C, tau_D, the div-div penalty, M^-1
+        cp = torch.tensor(ic["p"], device=dev)
+        cpo = torch.empty(cmesh.n_p, dtype=torch.float64, device=dev)
+        ctd = torch.empty(cmesh.n_cells, dtype=torch.float64, device=dev)
+        ops = {"pressure_gradient": lambda: cmesh.apply_pressure_gradient(cp, cr),
+               "velocity_divergence": lambda: cmesh.apply_velocity_divergence(cu, cpo),
+               "divdiv_tau": lambda: cmesh.divdiv_tau(cu, 0.05, ctd),
+               "divdiv": lambda: cmesh.apply_divdiv(ctd, cu, cr),
+               "inverse_mass": lambda: cmesh.apply_inverse_mass(cu, cr)}
+        op_ms = {}
+        for name, f in ops.items():
+            f()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                f()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            op_ms[name] = e0.elapsed_time(e1) / 3
+        extras["curved"]["projection_terms_ms"] = op_ms
+        del cmesh, cu, cr, cu32, cr32, cp, cpo, ctd
     if not args.no_extras and args.serving_requests > 0:
         # serving: seeded Poisson-arrival stream of channel instances (grid, k, nu mixed), each 10
         # velocity-residual applies + one mixed-precision solve to 1e-10; batched velocity rounds
