@@ -79,6 +79,7 @@ def lib():
         L.orc_velocity_divergence.argtypes = [P, _D, _D, _D, _I64, ctypes.c_int64, _D]
         L.orc_enrichment_active.argtypes = [P, _D, _D, ctypes.POINTER(ctypes.c_int32)]
         L.orc_cell_map.argtypes = [P, ctypes.c_int64, _D, _D, _D]
+        L.orc_cell_jacobians.argtypes = [P, ctypes.c_int64, ctypes.c_int64, _D, _D]
         L.orc_face_points.argtypes = [P, ctypes.c_int64, ctypes.c_int, _D]
         L.orc_viscous_multiscale.argtypes = [P, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_int, _I64,
                                              ctypes.c_int64, _D]
@@ -460,6 +461,17 @@ def cell_map(cfg, e, xi):
     det = ctypes.c_double()
     lib().orc_cell_map(ctypes.byref(p), int(e), _ptr(xi), _ptr(X), ctypes.byref(det))
     return X, det.value
+
+
+def cell_jacobians(cfg, e, pts):
+    """J[q][d][a] = dX_d / dxi_a of cell e at the reference points pts (npts, 3)."""
+    p = params(cfg)
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    J = np.zeros((len(pts), 3, 3))
+    rc = lib().orc_cell_jacobians(ctypes.byref(p), int(e), len(pts), _ptr(pts), _ptr(J))
+    if rc:
+        raise RuntimeError(f"orc_cell_jacobians failed: {rc}")
+    return J
 
 
 def face_points(cfg, e, f):

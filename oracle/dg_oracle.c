@@ -1496,6 +1496,22 @@ int orc_cell_map(const orc_params *P, int64_t e, const double *xi, double *X, do
   return 0;
 }
 
+/* Jacobians J[d][a] = dX_d / dxi_a of cell e at npts reference points (xi:
+ * [npts][3]; J: [npts][9]). */
+int orc_cell_jacobians(const orc_params *P, int64_t e, int64_t npts, const double *xi, double *J9) {
+  ctx C;
+  if (ctx_init(&C, P, NULL)) return -1;
+  if (e < 0 || e >= C.ncell) { ctx_free(&C); return -2; }
+  for (int64_t q = 0; q < npts; ++q) {
+    double X[3], J[3][3];
+    cell_map(&C, e, xi + 3 * q, X, J);
+    for (int d = 0; d < 3; ++d)
+      for (int a = 0; a < 3; ++a) J9[9 * q + 3 * d + a] = J[d][a];
+  }
+  ctx_free(&C);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Multiscale viscous operator (Sec. 2.2 and Sec. 4.2)                        */
 /* ------------------------------------------------------------------------ */

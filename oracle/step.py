@@ -12,8 +12,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (enriched_cells, enrichment_active, gauss, gauss_lobatto, lagrange, psi_point, psi_volume, psi_volume4,
-               vertex_eta, viscous_multiscale)
+from . import (cell_jacobians, enriched_cells, enrichment_active, gauss, gauss_lobatto, lagrange, psi_point,
+               psi_volume, psi_volume4, vertex_eta, viscous_multiscale)
 from .project import inverse_mass, mass_apply
 
 
@@ -103,7 +103,8 @@ def vorticity_rhs(cfg, u, tau):
     """b(v) = (v, curl u)_e for every velocity test function (N_B e_c, and the
     enrichment functions psi N^l_B e_c of an enriched cell whose enrichment is
     on) with the cell's velocity rule (nq_u^3, or nq_u x nq_wn x nq_u),
-    u = u_bar + psi sum_B N^l_B u~_B."""
+    u = u_bar + psi sum_B N^l_B u~_B.  On the curved-wall mesh (l = 0) the
+    gradients and |det J| of the isoparametric map enter point by point."""
     from .project import volume_rule, _nle, _vertex_grads
     nle = _nle(cfg)
     n3 = (cfg.k_u + 1) ** 3
@@ -117,6 +118,9 @@ def vorticity_rhs(cfg, u, tau):
     psi4 = psi_volume4(cfg, ecells, tau=tau) if ecells.size else None
     pts_e, wts_e = volume_rule(cfg)
     pts_r, wts_r = volume_rule(cfg.with_(nq_wn=cfg.nq_u))
+    curved = cfg.wall_amp != 0.0
+    if curved and nle != 1:
+        raise ValueError("curved meshes: l = 0 only")
     for e in range(cfg.ncell):
         ey = (e // cfg.nx) % cfg.ny
         h = (hx, eta[ey + 1] - eta[ey], hz)
@@ -124,8 +128,20 @@ def vorticity_rhs(cfg, u, tau):
         pts, wts = (pts_e, wts_e) if k is not None else (pts_r, wts_r)
         p4 = psi4[k] if k is not None else None
         ut = u[off + 3 * nle * k:off + 3 * nle * (k + 1)] if k is not None else None
-        V, _, grad = _cell_grads(cfg, u, e, pts, h, p4, ut)
-        cw = _curl(grad) * (wts * h[0] * h[1] * h[2])[:, None]
+        if curved:
+            # isoparametric cell: grad N = J^{-T} grad_xi N and w |det J| point by point
+            from .project import basis_at, _basis_grad_at
+            J = cell_jacobians(cfg, e, pts)
+            Ji = np.linalg.inv(J)                                                  # [q][a][d] = dxi_a / dx_d
+            G = np.einsum("qba,qad->qbd", _basis_grad_at(cfg, pts, (1.0, 1.0, 1.0)), Ji)
+            V = basis_at(cfg, pts)
+            grad = np.einsum("qbd,cb->qcd", G, u[e * 3 * n3:(e + 1) * 3 * n3].reshape(3, n3))
+            if p4 is not None:
+                grad += ut[None, :, None] * p4[:, None, 1:4]                      # grad (psi u~_c) = u~_c grad psi
+            cw = _curl(grad) * (wts * np.abs(np.linalg.det(J)))[:, None]
+        else:
+            V, _, grad = _cell_grads(cfg, u, e, pts, h, p4, ut)
+            cw = _curl(grad) * (wts * h[0] * h[1] * h[2])[:, None]
         b[e * 3 * n3:(e + 1) * 3 * n3] = (V.T @ cw).T.reshape(-1)
         if k is not None:
             phi = p4[:, 0:1] * (_vertex_grads(pts, h)[0] if nle == 8 else np.ones((len(pts), 1)))   # (npts, nle)

@@ -234,6 +234,16 @@ def test_enrichment_rows_with_linear_psi():
         for c in range(3):
             rows = d_pol[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
             assert abs(d_enr[off + 3 * k + c] - ps @ rows) <= 1e-12 * (np.abs(ps) @ np.abs(rows))
+    # the vorticity right-hand side (v, curl u)_e likewise
+    from oracle import step as OS
+    b_enr, b_pol = OS.vorticity_rhs(cfg, u_enr, tau), OS.vorticity_rhs(cfg, u_pol, tau)
+    assert np.abs(b_enr[:off] - b_pol[:off]).max() <= 1e-12 * np.abs(b_pol[:off]).max()
+    for k, e in enumerate(cells):
+        ps = np.array([O.psi_point(cfg, tau, int(e), (gl[B % n], gl[(B // n) % n], gl[B // (n * n)]))[0]
+                       for B in range(n3)])
+        for c in range(3):
+            rows = b_pol[(e * 3 + c) * n3:(e * 3 + c + 1) * n3]
+            assert abs(b_enr[off + 3 * k + c] - ps @ rows) <= 1e-12 * (np.abs(ps) @ np.abs(rows))
 
 
 def _numpy_mass(cfg, e, Y, nqx, nqy, psi_k=None):
@@ -302,3 +312,39 @@ def test_mass_matrix_on_curved_enriched_cells():
             assert abs(y[off + 3 * k + c] - ref[n3]) <= 1e-13 * scale
     xi, cond = OP.inverse_mass(cfg, y, psi, return_cond=True)
     assert np.abs(xi - x).max() <= 64 * 2.0 ** -52 * cond.max() * np.abs(x).max()
+
+
+def _coordinate_fields(cfg):
+    """Nodal x and y (the mapped coordinate) of every cell as [cell][m][j][i] arrays."""
+    n = cfg.k_u + 1
+    gl = _gl_nodes(n)
+    _, Y = _mapped_y(cfg)
+    hx = cfg.Lx / cfg.nx
+    xs = np.zeros((cfg.ncell, n, n, n))
+    ys = np.zeros((cfg.ncell, n, n, n))
+    for e in range(cfg.ncell):
+        xs[e] = (e % cfg.nx) * hx + hx * gl[None, None, :]
+        ys[e] = Y[e].T[None]
+    return xs, ys
+
+
+@pytest.mark.parametrize("name", ["k3", "k5", "k3_enriched"])
+def test_projected_vorticity_reproduces_constant_curls(name):
+    """omega = M^{-1} (v, curl u) (Sec. 4.2) of (0, x, 0), (y, 0, 0) and
+    (0, 0, y), y the mapped coordinate (all in the isoparametric velocity
+    space), is the constant curl (0, 0, 1), (0, 0, -1) and (1, 0, 0) at every
+    node, with vanishing enrichment coefficients where the cells are enriched."""
+    from oracle import step as OS
+    cfg = CURVED[name] if name in CURVED else MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8,
+                                                          k_p=2, nq_p=3)
+    n3 = (cfg.k_u + 1) ** 3
+    xs, ys = _coordinate_fields(cfg)
+    tau = np.random.default_rng(9).uniform(0.2, 2.0, cfg.n_tau)
+    for comp, field, curl in ((1, xs, (0.0, 0.0, 1.0)), (0, ys, (0.0, 0.0, -1.0)), (2, ys, (1.0, 0.0, 0.0))):
+        u = np.zeros(cfg.n_vel)
+        u[:cfg.ncell * 3 * n3].reshape(cfg.ncell, 3, n3)[:, comp] = field.reshape(cfg.ncell, n3)
+        om = OS.vorticity(cfg, u, tau)
+        blk = om[:cfg.ncell * 3 * n3].reshape(cfg.ncell, 3, n3)
+        for c in range(3):
+            assert np.abs(blk[:, c] - curl[c]).max() <= 1e-11, (comp, c)
+        assert np.abs(om[cfg.ncell * 3 * n3:]).max() <= 1e-9 if om.size > cfg.ncell * 3 * n3 else True
