@@ -424,13 +424,16 @@ int dg_apply_viscous_multiscale(const dg_mesh* mesh, const double* nut, const do
  * for every velocity test function (N_B e_c, and psi e_c in enriched cells),
  * u = u_bar + psi u~ (so curl u includes grad psi x u~), the cell's velocity
  * rule (nq_u^3; nq_u x nq_wn x nq_u in enriched cells).
- *   u, b: device, dg_num_dofs(mesh, 0) doubles, distinct.  Flat walls only.
+ *   u, b: device, dg_num_dofs(mesh, 0) doubles, distinct.  On the
+ *   curved-wall mesh (l = 0) grad u = J^{-T} grad_xi u and |det J| enter
+ *   per point.
  *   Errors: DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_HIP. */
 int dg_vorticity_rhs(const dg_mesh* mesh, const double* u, double* b, void* stream);
 
 /* omega = M^{-1} b with b from dg_vorticity_rhs: the L2 projection of curl u
  * onto the enriched velocity space (the inverse mass matrix of
- * dg_apply_inverse_mass).  u, omega: distinct device vectors. */
+ * dg_apply_inverse_mass; on the curved-wall mesh its per-cell CG).  u,
+ * omega: distinct device vectors. */
 int dg_vorticity(const dg_mesh* mesh, const double* u, double* omega, void* stream);
 
 /* Wall term of the pressure equation with the high-order Neumann data (paper

@@ -1,7 +1,7 @@
 // Pressure gradient and velocity divergence terms of the dual-splitting
 // scheme (arXiv 1705.08813, Sec. 4.2), the div-div penalty of its
-// projection step and the inverse velocity mass matrix on the curved-wall
-// mesh, FP64:
+// projection step, the inverse velocity mass matrix and the right-hand side
+// of the projected vorticity on the curved-wall mesh, FP64:
 //
 //   P: g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}     (velocity test functions)
 //   C: c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}    (pressure test functions)
@@ -702,10 +702,128 @@ __global__ __launch_bounds__(kCvThreads) void curved_invmass_kernel(const CvArgs
   }
 }
 
+// ---------------------------------------------------------------------------
+// Right-hand side of the projected vorticity (Sec. 4.2), b(v) = (v, curl u)_e
+// for v = N_B e_c and, in enriched cells, psi e_c; grad u = J^{-T} grad_xi u
+// point by point (plus u~ (x) grad psi in enriched cells).
+template <int NPU, int NQ, int NQY, bool ENR>
+__global__ __launch_bounds__(kCvThreads) void curved_vort_rhs_kernel(const CvArgs A, int layer_lo, int nlayers) {
+  constexpr int QY = ENR ? NQY : NQ;
+  constexpr int NU3 = NPU * NPU * NPU, NPT = NQ * QY * NQ;
+  constexpr auto& ux = ct::tab<NPU, NQ>;
+  constexpr auto& uy = ct::tab<NPU, QY>;
+  __shared__ double su[3 * NU3];
+  __shared__ double F[3][NPT];
+  __shared__ double red[3 * (kCvThreads / 64)];
+  __shared__ double sut[3];
+  const int tid = threadIdx.x;
+  const CvCell c = cv_cell<ENR>(A, blockIdx.x, layer_lo, nlayers);
+  for (int k = tid; k < 3 * NU3; k += kCvThreads) su[k] = A.in[c.e * 3 * NU3 + k];
+  if (tid < 3) sut[tid] = ENR ? A.in[A.ncell * 3 * NU3 + c.enr * 3 + tid] : 0.0;
+  __syncthreads();
+  const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
+  const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
+  double ev[3] = {0.0, 0.0, 0.0};
+  for (int q = tid; q < NPT; q += kCvThreads) {
+    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
+    double du[3][3] = {};  // [c][a] = d u_c / d xi_a
+    for (int k = 0; k < NPU; ++k)
+      for (int j = 0; j < NPU; ++j) {
+        const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
+        const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
+        for (int i = 0; i < NPU; ++i) {
+          const double b0 = ux.Sd[qx][i] * yz, b1 = ux.S[qx][i] * dyz, b2 = ux.S[qx][i] * ydz;
+          const int B = i + NPU * (j + NPU * k);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            const double uv = su[cc * NU3 + B];
+            du[cc][0] += b0 * uv;
+            du[cc][1] += b1 * uv;
+            du[cc][2] += b2 * uv;
+          }
+        }
+      }
+    const double* g = geo + q * 10;
+    double gr[3][3];  // [c][d] = d u_c / d x_d
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        gr[cc][d] = g[d] * du[cc][0] + g[3 + d] * du[cc][1] + g[6 + d] * du[cc][2];
+        if (ENR) gr[cc][d] += sut[cc] * ps[q * 4 + 1 + d];
+      }
+    const double w = g[9];
+    const double cu[3] = {w * (gr[2][1] - gr[1][2]), w * (gr[0][2] - gr[2][0]), w * (gr[1][0] - gr[0][1])};
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      F[cc][q] = cu[cc];
+      if (ENR) ev[cc] += ps[q * 4] * cu[cc];
+    }
+  }
+  __syncthreads();
+  double* o = A.out + c.e * 3 * NU3;
+  for (int it = tid; it < 3 * NU3; it += kCvThreads) {
+    const int cc = it / NU3, B = it - cc * NU3;
+    const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
+    double s = 0.0;
+    for (int qz = 0; qz < NQ; ++qz)
+      for (int qy = 0; qy < QY; ++qy) {
+        const double yz = uy.S[qy][j] * ux.S[qz][k];
+        for (int qx = 0; qx < NQ; ++qx) s += ux.S[qx][i] * yz * F[cc][qx + NQ * (qy + QY * qz)];
+      }
+    o[it] = s;
+  }
+  if (ENR) {
+    cv_block_sum<3>(ev, red, tid);
+    if (tid < 3) A.out[A.ncell * 3 * NU3 + c.enr * 3 + tid] = ev[tid];
+  }
+}
+
 }  // namespace
 
 // (k_u+1, nq_u, nq_wn) combinations of the velocity operators
 #define DG_CVD_COMBOS(X) X(3, 4, 8) X(3, 4, 4) X(4, 4, 8) X(4, 5, 8) X(4, 5, 5) X(5, 7, 8) X(6, 8, 8)
+
+int launch_vorticity_rhs_curved(const dg_mesh* m, const double* u, double* b, hipStream_t s) {
+  CvArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.upper_slot = m->upper_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  A.geo_stride = m->geo_stride;
+  A.fully_periodic = m->P.fully_periodic;
+  A.ncell = m->ncell;
+  A.geo = m->geo;
+  A.psi = m->psi;
+  A.in = u;
+  A.out = b;
+  if (!m->geo || m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "curved vorticity: l = 0 enrichment only");
+  const int lo = (m->P.fully_periodic || m->lower_slot < 0) ? 0 : 1;
+  const int hi = (m->P.fully_periodic || m->upper_slot < 0) ? m->P.ny - 1 : m->P.ny - 2;
+  const int nl = hi - lo + 1;
+  const int64_t nreg = nl > 0 ? (int64_t)m->P.nx * nl * m->P.nz : 0;
+  const bool any_w = m->nenr == 0;
+  const int nqw = m->P.nq_wn;
+#define X(p, q, w)                                                                                          \
+  if (m->np_u == p && m->P.nq_u == q && (any_w || nqw == w)) {                                              \
+    if (nreg > 0) {                                                                                         \
+      hipLaunchKernelGGL((curved_vort_rhs_kernel<p, q, w, false>), dim3((unsigned)nreg), dim3(kCvThreads), 0, s, \
+                         A, lo, nl);                                                                        \
+      const int rc = check_hip(hipGetLastError(), "curved vorticity kernel launch");                        \
+      if (rc) return rc;                                                                                    \
+    }                                                                                                       \
+    if (m->nenr > 0)                                                                                        \
+      hipLaunchKernelGGL((curved_vort_rhs_kernel<p, q, w, true>), dim3((unsigned)m->nenr), dim3(kCvThreads), 0, \
+                         s, A, 0, 0);                                                                       \
+    return check_hip(hipGetLastError(), "curved vorticity kernel launch");                                  \
+  }
+  DG_CVD_COMBOS(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "curved vorticity: (k_u+1, nq_u, nq_wn) combination not compiled");
+}
 
 int launch_inverse_mass_curved(const dg_mesh* m, const double* r, double* x, hipStream_t s) {
   CvArgs A;

@@ -319,6 +319,7 @@ MeshDev step_meshdev(const dg_mesh* m) {
 #define DG_STEP_COMBOS(X) X(3, 4, 8) X(3, 4, 4) X(4, 4, 8) X(4, 5, 8) X(4, 5, 5) X(5, 7, 8) X(6, 8, 8)
 
 int launch_vorticity_rhs(const dg_mesh* m, const double* u, double* b, hipStream_t s) {
+  if (m->curved) return launch_vorticity_rhs_curved(m, u, b, s);
   const MeshDev M = step_meshdev(m);
   const int np = m->np_u, nq = m->P.nq_u, nqw = m->P.nq_wn;
   const unsigned g = (unsigned)m->ncell;
@@ -378,14 +379,12 @@ extern "C" {
 int dg_vorticity_rhs(const dg_mesh* m, const double* u, double* b, void* stream) {
   if (!m || !u || !b) return set_error(DG_ERR_ARG, "mesh/u/b is NULL");
   if (u == b) return set_error(DG_ERR_ARG, "u and b must not alias");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the vorticity is built for flat walls only");
   return launch_vorticity_rhs(m, u, b, static_cast<hipStream_t>(stream));
 }
 
 int dg_vorticity(const dg_mesh* m, const double* u, double* omega, void* stream) {
   if (!m || !u || !omega) return set_error(DG_ERR_ARG, "mesh/u/omega is NULL");
   if (u == omega) return set_error(DG_ERR_ARG, "u and omega must not alias");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the vorticity is built for flat walls only");
   const hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = launch_vorticity_rhs(m, u, omega, s);
   if (!rc) rc = launch_inverse_mass(m, omega, omega, s);
