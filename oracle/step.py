@@ -162,7 +162,9 @@ def pressure_neumann(cfg, us, omegas, betas, f, tau):
     div F^c(u) = div(u (x) u), n the outward normal (-e_y on the lower wall,
     +e_y on the upper one), at the Gauss points of the velocity face rule
     (nq_u x nq_u) against the pressure basis; u_i = u_bar + psi sum_B N^l_B u~_B
-    and omega_i likewise in enriched cells (psi = 0 on the wall, grad psi not)."""
+    and omega_i likewise in enriched cells (psi = 0 on the wall, grad psi not).
+    On the curved-wall mesh (l = 0) n is the normal of the isoparametric wall
+    and every component of the flux enters."""
     from .project import _nle
     nle = _nle(cfg)
     if cfg.fully_periodic:
@@ -188,6 +190,10 @@ def pressure_neumann(cfg, us, omegas, betas, f, tau):
                 p4 = None
                 if k is not None and act[k]:
                     p4 = np.array([psi_point(cfg, tau, e, xi) for xi in pts])
+                if cfg.wall_amp != 0.0:
+                    hn = _curved_wall_flux(cfg, e, pts, gw, s, sg, us, omegas, betas, f, p4, k, off, nle)
+                    _add_wall_term(rhs, e, p3, pts, hn, nodes_p)
+                    continue
                 hn = np.zeros(len(pts))
                 for u, om, beta in zip(us, omegas, betas):
                     u = np.asarray(u, dtype=np.float64)
@@ -208,6 +214,44 @@ def pressure_neumann(cfg, us, omegas, betas, f, tau):
                     Np = np.einsum("m,j,i->mji", vz, vy, vx).reshape(-1)
                     rhs[e * p3:(e + 1) * p3] += wts[qi] * hn[qi] * Np
     return rhs
+
+
+def _curved_wall_flux(cfg, e, pts, gw, s, sg, us, omegas, betas, f, p4, k, off, nle):
+    """h_N w dA at the wall-face points pts of curved cell e: the full normal of
+    the isoparametric wall, n dA = |det J| J^{-T} (sg e_y) dA_ref (Nanson), and
+    div(u (x) u) = (u . grad) u + u div u, all three components."""
+    from .project import basis_at, _basis_grad_at
+    J = cell_jacobians(cfg, e, pts)
+    Ji = np.linalg.inv(J)
+    wref = np.array([gw[a] * gw[c] for c in range(cfg.nq_u) for a in range(cfg.nq_u)])
+    nwda = (sg * wref * np.abs(np.linalg.det(J)))[:, None] * Ji[:, 1, :]
+    V = basis_at(cfg, pts)
+    G = np.einsum("qba,qad->qbd", _basis_grad_at(cfg, pts, (1.0, 1.0, 1.0)), Ji)
+    n3 = (cfg.k_u + 1) ** 3
+    hvec = np.zeros((len(pts), 3))
+    for u, om, beta in zip(us, omegas, betas):
+        u = np.asarray(u, dtype=np.float64)
+        om = np.asarray(om, dtype=np.float64)
+        U = u[e * 3 * n3:(e + 1) * 3 * n3].reshape(3, n3)
+        W = om[e * 3 * n3:(e + 1) * 3 * n3].reshape(3, n3)
+        val, g, go = V @ U.T, np.einsum("qbd,cb->qcd", G, U), np.einsum("qbd,cb->qcd", G, W)
+        if p4 is not None:
+            ut, ot = u[off + 3 * k:off + 3 * k + 3], om[off + 3 * k:off + 3 * k + 3]
+            val += p4[:, 0:1] * ut[None, :]
+            g += ut[None, :, None] * p4[:, None, 1:4]
+            go += ot[None, :, None] * p4[:, None, 1:4]
+        div = g[:, 0, 0] + g[:, 1, 1] + g[:, 2, 2]
+        conv = np.einsum("qij,qj->qi", g, val) + val * div[:, None]
+        hvec += beta * (conv + cfg.nu * _curl(go))
+    return -np.einsum("qi,qi->q", hvec - np.asarray(f, dtype=np.float64)[None, :], nwda)
+
+
+def _add_wall_term(rhs, e, p3, pts, hn_wda, nodes_p):
+    for qi, xi in enumerate(pts):
+        vx = lagrange(nodes_p, xi[0])[0]
+        vy = lagrange(nodes_p, xi[1])[0]
+        vz = lagrange(nodes_p, xi[2])[0]
+        rhs[e * p3:(e + 1) * p3] += hn_wda[qi] * np.einsum("m,j,i->mji", vz, vy, vx).reshape(-1)
 
 
 def dual_splitting_step(cfg, tau, u_n, u_nm1, dt, order=2, f=(0.0, 0.0, 0.0), dt_over_cr=None,

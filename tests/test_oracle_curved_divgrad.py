@@ -348,3 +348,56 @@ def test_projected_vorticity_reproduces_constant_curls(name):
         for c in range(3):
             assert np.abs(blk[:, c] - curl[c]).max() <= 1e-11, (comp, c)
         assert np.abs(om[cfg.ncell * 3 * n3:]).max() <= 1e-9 if om.size > cfg.ncell * 3 * n3 else True
+
+
+@pytest.mark.parametrize("name", ["k3_enriched", "k5"])
+def test_neumann_wall_term_on_the_curved_wall(name):
+    """Wall term of the pressure equation (eq. bc_d_pres) on the curved mesh,
+    summed over each wall cell's pressure block (sum_B N^p_B = 1), so that it
+    is a face integral computable from the map:
+      (a) constant u, omega = 0: f . int n dA = f_x hz dy_w - f_y hx hz (lower
+          wall; n dA = (dy_w/dx, -1, 0) dx dz), f_y hx hz on the upper wall;
+      (b) omega = (0, 0, y): curl omega = e_x, so -nu hz dy_w (0 above);
+      (c) u = (x, 0, 0): div(u (x) u) = 2 x e_x, so -int 2 x (dy_w/dx) dx dz."""
+    from oracle import step as OS
+    cfg = CURVED[name] if name in CURVED else MeshConfig(nx=4, ny=3, nz=2, wall_amp=0.3, k_u=3, nq_u=5, nq_wn=8,
+                                                          k_p=2, nq_p=3)
+    n, p3 = cfg.k_u + 1, (cfg.k_p + 1) ** 3
+    n3 = n ** 3
+    hx, hz = cfg.Lx / cfg.nx, cfg.Lz / cfg.nz
+    gl = _gl_nodes(n)
+    tau = np.random.default_rng(10).uniform(0.2, 2.0, cfg.n_tau)
+    xs, ys = _coordinate_fields(cfg)
+    zero = np.zeros(cfg.n_vel)
+    yw = lambda x: -1.0 + cfg.wall_amp * np.cos(2.0 * math.pi * x / cfg.Lx)   # noqa: E731
+    gq, wq = np.polynomial.legendre.leggauss(2 * n + 2)
+    gq, wq = 0.5 * (gq + 1.0), 0.5 * wq
+
+    def cell_sums(rhs, ey):
+        return np.array([[rhs[(ex + cfg.nx * (ey + cfg.ny * ez)) * p3:(ex + cfg.nx * (ey + cfg.ny * ez) + 1) * p3].sum()
+                          for ex in range(cfg.nx)] for ez in range(cfg.nz)])
+
+    dyw = np.array([yw((ex + 1) * hx) - yw(ex * hx) for ex in range(cfg.nx)])[None, :]
+    # (a)
+    f = (0.7, -1.3, 0.4)
+    u = _const_velocity(cfg, (0.3, -0.7, 1.1))
+    r = OS.pressure_neumann(cfg, [u], [zero], (1.0,), f, tau)
+    assert np.abs(cell_sums(r, 0) - (f[0] * hz * dyw - f[1] * hx * hz)).max() <= 1e-12
+    assert np.abs(cell_sums(r, cfg.ny - 1) - f[1] * hx * hz).max() <= 1e-12
+    # (b)
+    om = np.zeros(cfg.n_vel)
+    om[:cfg.ncell * 3 * n3].reshape(cfg.ncell, 3, n3)[:, 2] = ys.reshape(cfg.ncell, n3)
+    r = OS.pressure_neumann(cfg, [zero], [om], (1.0,), (0.0, 0.0, 0.0), tau)
+    assert np.abs(cell_sums(r, 0) + cfg.nu * hz * dyw).max() <= 1e-12 * cfg.nu
+    assert np.abs(cell_sums(r, cfg.ny - 1)).max() <= 1e-12 * cfg.nu
+    # (c): the interpolated wall y_h(x) of each lower cell, its x-derivative at Gauss points
+    ux = np.zeros(cfg.n_vel)
+    ux[:cfg.ncell * 3 * n3].reshape(cfg.ncell, 3, n3)[:, 0] = xs.reshape(cfg.ncell, n3)
+    r = OS.pressure_neumann(cfg, [ux], [zero], (1.0,), (0.0, 0.0, 0.0), tau)
+    _, dl = _lagrange(gl, gq)
+    ref = np.zeros((1, cfg.nx))
+    for ex in range(cfg.nx):
+        dydxi = dl @ yw(ex * hx + hx * gl)                           # d y_h / d xi along the wall face
+        ref[0, ex] = -hz * np.sum(wq * 2.0 * (ex * hx + hx * gq) * dydxi)
+    assert np.abs(cell_sums(r, 0) - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(cell_sums(r, cfg.ny - 1)).max() <= 1e-12 * np.abs(ref).max()
