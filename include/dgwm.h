@@ -442,7 +442,9 @@ int dg_vorticity(const dg_mesh* mesh, const double* u, double* omega, void* stre
  *   h_N = -( sum_i beta[i] (div(u_i (x) u_i) + nu curl omega_i) - f ) . n
  * for the nhist (1 or 2) previous velocities u_i and their vorticities
  * omega_i (dg_vorticity), n the outward wall normal (-e_y lower, +e_y upper
- * wall), evaluated at the Gauss points of the velocity face rule (nq_u x
+ * wall; on the curved-wall mesh, l = 0, the normal of the isoparametric wall,
+ * +-|det J| J^{-T} e_y normalised, with all three flux components),
+ * evaluated at the Gauss points of the velocity face rule (nq_u x
  * nq_u) with u = u_bar + psi u~ (psi vanishes on the wall, grad psi does not)
  * and tested with the pressure basis; only the wall cells' pressure rows
  * change.  Nothing is added on a fully periodic box.

@@ -240,6 +240,8 @@ int launch_divgrad(const dg_mesh* m, bool divergence, const double* in, double* 
 int launch_divgrad_curved(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s);
 int launch_inverse_mass_curved(const dg_mesh* m, const double* r, double* x, hipStream_t s);
 int launch_vorticity_rhs_curved(const dg_mesh* m, const double* u, double* b, hipStream_t s);
+int launch_pressure_neumann_curved(const dg_mesh* m, int nh, const double* const* us, const double* const* oms,
+                                   const double* beta, const double* f, double* rhs, hipStream_t s);
 // element-wise projection step: (M + D) x = M u_hat - scale g per cell, preconditioned CG in each cell
 // projection step: spectral tables of every layer (direct solves)
 int spectral_layers(const dg_mesh& m, std::vector<int>* map, std::vector<double>* heights);

@@ -1,7 +1,8 @@
 // Pressure gradient and velocity divergence terms of the dual-splitting
 // scheme (arXiv 1705.08813, Sec. 4.2), the div-div penalty of its
-// projection step, the inverse velocity mass matrix and the right-hand side
-// of the projected vorticity on the curved-wall mesh, FP64:
+// projection step, the inverse velocity mass matrix, the right-hand side of
+// the projected vorticity and the pressure Neumann wall term on the
+// curved-wall mesh, FP64:
 //
 //   P: g(v) = -(div v, p)_e + (v . n, {{p}})_{boundary of e}     (velocity test functions)
 //   C: c(q) = -(grad q, u)_e + (q, {{u}} . n)_{boundary of e}    (pressure test functions)
@@ -779,6 +780,106 @@ __global__ __launch_bounds__(kCvThreads) void curved_vort_rhs_kernel(const CvArg
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wall term of the pressure equation with the high-order Neumann data
+// (Sec. 4.1, eq. bc_d_pres) on the curved-wall mesh, ADDED into rhs:
+//   rhs(q) += int_wall q h_N dA,  h_N = -(sum_h beta_h (div(u_h (x) u_h) + nu curl omega_h) - f) . n,
+// div(u (x) u) = (u . grad) u + u div u, n dA = +-|det J| J^{-T} e_y dA_ref on the
+// wall faces (all three components: the lower wall is curved).  One workgroup
+// per wall cell, one thread per face point; each cell adds only into its own
+// wall-face layer.
+struct CvNeuArgs {
+  const double* u[2];
+  const double* om[2];
+  double beta[2], f[3], nu;
+  int nh;
+};
+
+template <int NPU, int NPP, int NQ, int NQY>
+__global__ __launch_bounds__(64) void curved_neumann_kernel(const CvArgs A, const CvNeuArgs N, double* rhs) {
+  constexpr int NU3 = NPU * NPU * NPU, NP3 = NPP * NPP * NPP, NF = NQ * NQ;
+  constexpr auto& ux = ct::tab<NPU, NQ>;
+  constexpr auto& px = ct::tab<NPP, NQ>;
+  __shared__ double su[2][2][3 * NU3];  // [history][u, omega]
+  __shared__ double st[2][2][3];
+  __shared__ double H[NF];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x, wall = b / (A.nx * A.nz), col = b - wall * A.nx * A.nz;
+  const int ex = col % A.nx, ez = col / A.nx, ey = wall ? A.ny - 1 : 0, s = wall;
+  const int64_t e = ex + (int64_t)A.nx * (ey + (int64_t)A.ny * ez);
+  const int64_t enr = cv_enr(A, ex, ey, ez);
+  const int64_t n_poly = A.ncell * 3 * NU3;
+  for (int h = 0; h < N.nh; ++h)
+    for (int k = tid; k < 3 * NU3; k += 64) {
+      su[h][0][k] = N.u[h][e * 3 * NU3 + k];
+      su[h][1][k] = N.om[h][e * 3 * NU3 + k];
+    }
+  if (tid < 6 * N.nh) {
+    const int h = tid / 6, w = (tid / 3) % 2, cc = tid % 3;
+    st[h][w][cc] = enr >= 0 ? (w ? N.om[h] : N.u[h])[n_poly + enr * 3 + cc] : 0.0;
+  }
+  __syncthreads();
+  const int qyc = enr >= 0 ? NQY : NQ;
+  const double* g = A.geo + (e * A.geo_stride + psi_face_offset(NQ, qyc, 2 + s)) * 10;
+  const double* ps = enr >= 0 ? A.psi + (enr * A.psi_pts + psi_face_offset(NQ, NQY, 2 + s)) * 4 : nullptr;
+  const double* nd = s ? ux.nd1 : ux.nd0;
+  const int jf = s ? NPU - 1 : 0;
+  for (int q = tid; q < NF; q += 64) {
+    const int qx = q % NQ, qz = q / NQ;
+    const double* gq = g + q * 10;
+    double hv[3] = {0.0, 0.0, 0.0};
+    for (int h = 0; h < N.nh; ++h) {
+      double val[3] = {}, du[2][3][3] = {};  // [u, omega][c][a]
+      for (int k = 0; k < NPU; ++k)
+        for (int i = 0; i < NPU; ++i) {
+          const double bxz = ux.S[qx][i] * ux.S[qz][k], dx = ux.Sd[qx][i] * ux.S[qz][k];
+          const double dz = ux.S[qx][i] * ux.Sd[qz][k];
+          for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+              const double v = su[h][w][cc * NU3 + i + NPU * (jf + NPU * k)];
+              if (w == 0) val[cc] += bxz * v;
+              du[w][cc][0] += dx * v;
+              du[w][cc][2] += dz * v;
+              double dy = 0.0;
+              for (int j = 0; j < NPU; ++j) dy += nd[j] * su[h][w][cc * NU3 + i + NPU * (j + NPU * k)];
+              du[w][cc][1] += bxz * dy;
+            }
+        }
+      double gr[2][3][3];
+      for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            gr[w][cc][d] = gq[d] * du[w][cc][0] + gq[3 + d] * du[w][cc][1] + gq[6 + d] * du[w][cc][2];
+            if (ps) gr[w][cc][d] += st[h][w][cc] * ps[q * 4 + 1 + d];
+          }
+      if (ps)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) val[cc] += ps[q * 4] * st[h][0][cc];
+      const double div = gr[0][0][0] + gr[0][1][1] + gr[0][2][2];
+      const double curl[3] = {gr[1][2][1] - gr[1][1][2], gr[1][0][2] - gr[1][2][0], gr[1][1][0] - gr[1][0][1]};
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        hv[cc] += N.beta[h] * (gr[0][cc][0] * val[0] + gr[0][cc][1] * val[1] + gr[0][cc][2] * val[2] +
+                               val[cc] * div + N.nu * curl[cc]);
+    }
+    // n w dA = +-(w dA) J^{-T} e_y / |J^{-T} e_y|
+    const double nrm = sqrt(gq[3] * gq[3] + gq[4] * gq[4] + gq[5] * gq[5]);
+    const double sc = (s ? 1.0 : -1.0) * gq[9] / nrm;
+    H[q] = -sc * ((hv[0] - N.f[0]) * gq[3] + (hv[1] - N.f[1]) * gq[4] + (hv[2] - N.f[2]) * gq[5]);
+  }
+  __syncthreads();
+  for (int l = tid; l < NPP * NPP; l += 64) {
+    const int i = l % NPP, k = l / NPP;
+    double v = 0.0;
+    for (int qz = 0; qz < NQ; ++qz)
+      for (int qx = 0; qx < NQ; ++qx) v += px.S[qx][i] * px.S[qz][k] * H[qx + NQ * qz];
+    rhs[e * NP3 + cv_layer<NPP>(1, s, i, k)] += v;
+  }
+}
+
 }  // namespace
 
 // (k_u+1, nq_u, nq_wn) combinations of the velocity operators
@@ -916,6 +1017,46 @@ int launch_divdiv_curved(const dg_mesh* m, bool tau, const double* u, const doub
 
 // (k_u+1, k_p+1, nq_u, nq_wn) combinations: the velocity ones with k_p = k_u - 1
 #define DG_CV_COMBOS(X) X(3, 2, 4, 8) X(3, 2, 4, 4) X(4, 3, 4, 8) X(4, 3, 5, 8) X(4, 3, 5, 5) X(5, 4, 7, 8) X(6, 5, 8, 8)
+
+int launch_pressure_neumann_curved(const dg_mesh* m, int nh, const double* const* us, const double* const* oms,
+                                   const double* beta, const double* f, double* rhs, hipStream_t s) {
+  CvArgs A;
+  A.nx = m->P.nx;
+  A.ny = m->P.ny;
+  A.nz = m->P.nz;
+  A.lower_slot = m->lower_slot;
+  A.upper_slot = m->upper_slot;
+  A.nslots = m->n_enr_layers;
+  A.psi_pts = m->psi_pts;
+  A.geo_stride = m->geo_stride;
+  A.fully_periodic = m->P.fully_periodic;
+  A.ncell = m->ncell;
+  A.geo = m->geo;
+  A.psi = m->psi;
+  A.in = nullptr;
+  A.out = nullptr;
+  if (!m->geo || m->nle != 1) return set_error(DG_ERR_UNSUPPORTED, "curved Neumann data: l = 0 enrichment only");
+  CvNeuArgs N{};
+  for (int h = 0; h < nh; ++h) {
+    N.u[h] = us[h];
+    N.om[h] = oms[h];
+    N.beta[h] = beta[h];
+  }
+  N.nh = nh;
+  for (int d = 0; d < 3; ++d) N.f[d] = f ? f[d] : 0.0;
+  N.nu = m->P.nu;
+  const unsigned g = (unsigned)(2 * m->P.nx * m->P.nz);
+  const bool any_w = m->nenr == 0;
+  const int nqw = m->P.nq_wn;
+#define X(pu, pp, q, w)                                                                                  \
+  if (m->np_u == pu && m->np_p == pp && m->P.nq_u == q && (any_w || nqw == w)) {                          \
+    hipLaunchKernelGGL((curved_neumann_kernel<pu, pp, q, w>), dim3(g), dim3(64), 0, s, A, N, rhs);       \
+    return check_hip(hipGetLastError(), "curved pressure Neumann launch");                               \
+  }
+  DG_CV_COMBOS(X)
+#undef X
+  return set_error(DG_ERR_UNSUPPORTED, "curved Neumann data: (k_u+1, k_p+1, nq_u, nq_wn) combination not compiled");
+}
 
 int launch_divgrad_curved(const dg_mesh* m, bool divergence, const double* in, double* out, hipStream_t s) {
   CvArgs A;

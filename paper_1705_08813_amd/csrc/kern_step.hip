@@ -397,7 +397,8 @@ int dg_pressure_neumann(const dg_mesh* m, int32_t nhist, const double* const* u,
   if (nhist < 1 || nhist > 2) return set_error(DG_ERR_ARG, "nhist must be 1 or 2");
   for (int h = 0; h < nhist; ++h)
     if (!u[h] || !omega[h]) return set_error(DG_ERR_ARG, "a velocity or vorticity vector is NULL");
-  if (m->curved) return set_error(DG_ERR_UNSUPPORTED, "the Neumann data is built for flat walls only");
+  if (m->curved)
+    return launch_pressure_neumann_curved(m, nhist, u, omega, beta, f, rhs, static_cast<hipStream_t>(stream));
   return launch_pressure_neumann(m, nhist, u, omega, beta, f, rhs, static_cast<hipStream_t>(stream));
 }
 
