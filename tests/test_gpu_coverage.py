@@ -65,7 +65,8 @@ def test_every_entry_point_accepts_the_combination(combo, kind):
 @pytest.mark.parametrize("combo", COMBOS, ids=[f"np{a}_nq{b}_nw{c}" for a, b, c in COMBOS])
 def test_curved_entry_points_accept_the_combination(combo):
     """The entry points built for the curved-wall mesh (velocity residual, P, C,
-    tau_D, the div-div penalty, the inverse mass) on every compiled combination."""
+    tau_D, the div-div penalty, the inverse mass, the vorticity, the Neumann
+    wall term) on every compiled combination."""
     npu, nq, nqw = combo
     cfg = MeshConfig(nx=2, ny=3, nz=2, wall_amp=0.3, k_u=npu - 1, nq_u=nq, nq_wn=nqw, k_p=npu - 2, nq_p=npu - 1,
                      nu=1.0 / 400)
@@ -75,6 +76,8 @@ def test_curved_entry_points_accept_the_combination(combo):
     u = torch.tensor(0.3 * rng.uniform(-1, 1, cfg.n_vel), device="cuda")
     p = torch.tensor(rng.uniform(-1, 1, cfg.n_p), device="cuda")
     td = mesh.divdiv_tau(u, 0.05)
+    om = mesh.vorticity(u)
     outs = [mesh.apply_velocity_residual(u), mesh.apply_velocity_residual(u.float()), mesh.apply_pressure_gradient(p),
-            mesh.apply_velocity_divergence(u), td, mesh.apply_divdiv(td, u), mesh.apply_inverse_mass(u)]
+            mesh.apply_velocity_divergence(u), td, mesh.apply_divdiv(td, u), mesh.apply_inverse_mass(u), om,
+            mesh.pressure_neumann([u], [om], (1.0,))]
     assert all(_finite(o) for o in outs)
