@@ -25,7 +25,9 @@ keep their values, since their space does not change.
 
 psi_old and psi_new are given as values at those quadrature points
 ([enriched cell][point], x fastest, then the wall-normal rule, then z), so
-that tests can also feed synthetic fields.  Flat (box) meshes only.
+that tests can also feed synthetic fields.  The L2 projection and the
+projection step are for flat (box) meshes; the mass matrix and its inverse
+also take the curved-wall mesh (l = 0, |det J| per point).
 """
 from __future__ import annotations
 

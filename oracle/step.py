@@ -6,7 +6,9 @@ TEST INFRASTRUCTURE ONLY (never used by the product).
 
 Library solvers serve as the solution steps: SciPy's GMRES for the
 Helmholtz equation, NumPy's dense least squares for the singular pressure
-equation on small meshes.  Flat (box) meshes only.
+equation on small meshes.  The vorticity right-hand side and the Neumann
+wall term also take the curved-wall mesh (l = 0); the rest is for flat
+(box) meshes.
 """
 from __future__ import annotations
 
