@@ -494,39 +494,63 @@ __global__ __launch_bounds__(kCvThreads) void curved_divdiv_kernel(const CvArgs 
 constexpr int kCvMaxIt = 100;
 constexpr double kCvTol = 1e-15;
 
+// Y = A P for NV vectors, A_BB' = sum_q W(q) N_B(q) N_B'(q): interpolation to the
+// points and the transposed projection, each by three 1-D sweeps (x, y, z);
+// X1 (NV NPU^2 NQ) and X2 (NV NPU QY NQ) are scratch.
 template <int NPU, int NQ, int QY, int NV>
 __device__ __forceinline__ void cv_mass_apply(const double (*P)[NPU * NPU * NPU], double (*Y)[NPU * NPU * NPU],
-                                              double (*T)[NQ * QY * NQ], const double* W, int tid) {
+                                              double (*T)[NQ * QY * NQ], const double* W, double* X1, double* X2,
+                                              int tid) {
   constexpr int NU3 = NPU * NPU * NPU, NPT = NQ * QY * NQ;
+  constexpr int S1 = NPU * NPU * NQ, S2 = NPU * QY * NQ;
   constexpr auto& ux = ct::tab<NPU, NQ>;
   constexpr auto& uy = ct::tab<NPU, QY>;
-  for (int q = tid; q < NPT; q += kCvThreads) {
-    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
-    double v[NV] = {};
-    for (int k = 0; k < NPU; ++k)
-      for (int j = 0; j < NPU; ++j) {
-        const double fy = uy.S[qy][j] * ux.S[qz][k];
-        for (int i = 0; i < NPU; ++i) {
-          const double b = ux.S[qx][i] * fy;
-          const int B = i + NPU * (j + NPU * k);
-#pragma unroll
-          for (int r = 0; r < NV; ++r) v[r] += b * P[r][B];
-        }
-      }
-#pragma unroll
-    for (int r = 0; r < NV; ++r) T[r][q] = W[q] * v[r];
+  // x: X1[r][k][j][qx] = sum_i S[qx][i] P[r][i, j, k]
+  for (int it = tid; it < NV * S1; it += kCvThreads) {
+    const int r = it / S1, t = it - r * S1, qx = t % NQ, jk = t / NQ;
+    double v = 0.0;
+    for (int i = 0; i < NPU; ++i) v += ux.S[qx][i] * P[r][i + NPU * jk];
+    X1[it] = v;
   }
   __syncthreads();
+  // y: X2[r][k][qy][qx] = sum_j Sy[qy][j] X1[r][k][j][qx]
+  for (int it = tid; it < NV * S2; it += kCvThreads) {
+    const int r = it / S2, t = it - r * S2, qx = t % NQ, qy = (t / NQ) % QY, k = t / (NQ * QY);
+    double v = 0.0;
+    for (int j = 0; j < NPU; ++j) v += uy.S[qy][j] * X1[r * S1 + qx + NQ * (j + NPU * k)];
+    X2[it] = v;
+  }
+  __syncthreads();
+  // z, times W: T[r][q] = W(q) sum_k S[qz][k] X2[r][k][qy][qx]
+  for (int it = tid; it < NV * NPT; it += kCvThreads) {
+    const int r = it / NPT, q = it - r * NPT, qxy = q % (NQ * QY), qz = q / (NQ * QY);
+    double v = 0.0;
+    for (int k = 0; k < NPU; ++k) v += ux.S[qz][k] * X2[r * S2 + qxy + NQ * QY * k];
+    T[r][q] = W[q] * v;
+  }
+  __syncthreads();
+  // transposed x: X2[r][qz][qy][i] = sum_qx S[qx][i] T[r][qx, qy, qz]
+  for (int it = tid; it < NV * S2; it += kCvThreads) {
+    const int r = it / S2, t = it - r * S2, i = t % NPU, qyz = t / NPU;
+    double v = 0.0;
+    for (int qx = 0; qx < NQ; ++qx) v += ux.S[qx][i] * T[r][qx + NQ * qyz];
+    X2[it] = v;
+  }
+  __syncthreads();
+  // transposed y: X1[r][qz][j][i] = sum_qy Sy[qy][j] X2[r][qz][qy][i]
+  for (int it = tid; it < NV * S1; it += kCvThreads) {
+    const int r = it / S1, t = it - r * S1, i = t % NPU, j = (t / NPU) % NPU, qz = t / (NPU * NPU);
+    double v = 0.0;
+    for (int qy = 0; qy < QY; ++qy) v += uy.S[qy][j] * X2[r * S2 + i + NPU * (qy + QY * qz)];
+    X1[it] = v;
+  }
+  __syncthreads();
+  // transposed z: Y[r][i, j, k] = sum_qz S[qz][k] X1[r][qz][j][i]
   for (int it = tid; it < NV * NU3; it += kCvThreads) {
-    const int r = it / NU3, B = it - r * NU3;
-    const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
-    double s = 0.0;
-    for (int qz = 0; qz < NQ; ++qz)
-      for (int qy = 0; qy < QY; ++qy) {
-        const double yz = uy.S[qy][j] * ux.S[qz][k];
-        for (int qx = 0; qx < NQ; ++qx) s += ux.S[qx][i] * yz * T[r][qx + NQ * (qy + QY * qz)];
-      }
-    Y[r][B] = s;
+    const int r = it / NU3, B = it - r * NU3, ij = B % (NPU * NPU), k = B / (NPU * NPU);
+    double v = 0.0;
+    for (int qz = 0; qz < NQ; ++qz) v += ux.S[qz][k] * X1[r * S1 + ij + NPU * NPU * qz];
+    Y[r][B] = v;
   }
   __syncthreads();
 }
@@ -570,6 +594,7 @@ __global__ __launch_bounds__(kCvThreads) void curved_invmass_kernel(const CvArgs
   __shared__ double T[NV][NPT];
   __shared__ double W[NPT], PS[ENR ? NPT : 1], B0[ENR ? NU3 : 1];
   __shared__ double Mi[NPU * NPU];
+  __shared__ double X1[NV * NPU * NPU * NQ], X2[NV * NPU * QY * NQ];
   __shared__ double red[3 * NV * (kCvThreads / 64)];
   __shared__ double rhs_e[3];
   const int tid = threadIdx.x;
@@ -633,7 +658,7 @@ __global__ __launch_bounds__(kCvThreads) void curved_invmass_kernel(const CvArgs
 #pragma unroll
     for (int r = 0; r < NV; ++r) all = all && done[r];
     if (all) break;
-    cv_mass_apply<NPU, NQ, QY, NV>(P, AP, T, W, tid);
+    cv_mass_apply<NPU, NQ, QY, NV>(P, AP, T, W, X1, X2, tid);
     double pa[NV] = {};
     for (int k = tid; k < NV * NU3; k += kCvThreads) {
       const int r = k / NU3, B = k - r * NU3;
