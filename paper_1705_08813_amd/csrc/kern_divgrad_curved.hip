@@ -22,9 +22,10 @@
 // Gauss-Lobatto nodal basis has its face values on that layer) against
 // w dA n {{p}} or w dA {{u}} . n at the face points.  One workgroup per cell
 // with the cell's block accumulated in LDS and written once; the 1-D tables
-// of both bases at both rules are compile-time constants.  Cost is not the
-// concern here (the curved configuration's hot path is the velocity
-// operator): the contractions are direct sums over the points.
+// of both bases at both rules are compile-time constants.  The volume terms
+// of P and C interpolate and integrate by 1-D sweeps; the face terms and the
+// other curved kernels use direct sums over the points (the curved
+// configuration's hot path is the velocity operator).
 #include "ctab.h"
 #include "kern_common.h"
 
@@ -120,6 +121,69 @@ __device__ __forceinline__ void cv_block_sum(double (&v)[NV], double* red, int t
   }
 }
 
+// Tensor sweeps over NV nodal fields of NP^3 (vector stride NP^3): values at
+// the NQ x QY x NQ points, and the transposed gradient integrals
+//   Y[r][B] = sum_q sum_a d_a N_B(q) F[r][a][q]   (F: [NV][3][NPT]),
+// each as 1-D sweeps x, y, z; X1 (NV NP^2 NQ) and X2 (NV NP QY NQ) are scratch.
+template <int NP, int NQ, int QY, int NV>
+__device__ __forceinline__ void cv_interp(const double* P, double* T, double* X1, double* X2, int tid) {
+  constexpr int NP3 = NP * NP * NP, NPT = NQ * QY * NQ, S1 = NP * NP * NQ, S2 = NP * QY * NQ;
+  constexpr auto& tx = ct::tab<NP, NQ>;
+  constexpr auto& ty = ct::tab<NP, QY>;
+  for (int it = tid; it < NV * S1; it += kCvThreads) {
+    const int r = it / S1, t = it - r * S1, qx = t % NQ, jk = t / NQ;
+    double v = 0.0;
+    for (int i = 0; i < NP; ++i) v += tx.S[qx][i] * P[r * NP3 + i + NP * jk];
+    X1[it] = v;
+  }
+  __syncthreads();
+  for (int it = tid; it < NV * S2; it += kCvThreads) {
+    const int r = it / S2, t = it - r * S2, qx = t % NQ, qy = (t / NQ) % QY, k = t / (NQ * QY);
+    double v = 0.0;
+    for (int j = 0; j < NP; ++j) v += ty.S[qy][j] * X1[r * S1 + qx + NQ * (j + NP * k)];
+    X2[it] = v;
+  }
+  __syncthreads();
+  for (int it = tid; it < NV * NPT; it += kCvThreads) {
+    const int r = it / NPT, q = it - r * NPT, qxy = q % (NQ * QY), qz = q / (NQ * QY);
+    double v = 0.0;
+    for (int k = 0; k < NP; ++k) v += tx.S[qz][k] * X2[r * S2 + qxy + NQ * QY * k];
+    T[it] = v;
+  }
+  __syncthreads();
+}
+
+template <int NP, int NQ, int QY, int NV>
+__device__ __forceinline__ void cv_project_grad(const double* F, double* Y, double* X1, double* X2, int tid) {
+  constexpr int NP3 = NP * NP * NP, NPT = NQ * QY * NQ, S1 = NP * NP * NQ, S2 = NP * QY * NQ;
+  constexpr auto& tx = ct::tab<NP, NQ>;
+  constexpr auto& ty = ct::tab<NP, QY>;
+  for (int a = 0; a < 3; ++a) {
+    for (int it = tid; it < NV * S2; it += kCvThreads) {
+      const int r = it / S2, t = it - r * S2, i = t % NP, qyz = t / NP;
+      const double* f = F + (r * 3 + a) * NPT + NQ * qyz;
+      double v = 0.0;
+      for (int qx = 0; qx < NQ; ++qx) v += (a == 0 ? tx.Sd[qx][i] : tx.S[qx][i]) * f[qx];
+      X2[it] = v;
+    }
+    __syncthreads();
+    for (int it = tid; it < NV * S1; it += kCvThreads) {
+      const int r = it / S1, t = it - r * S1, i = t % NP, j = (t / NP) % NP, qz = t / (NP * NP);
+      double v = 0.0;
+      for (int qy = 0; qy < QY; ++qy) v += (a == 1 ? ty.Sd[qy][j] : ty.S[qy][j]) * X2[r * S2 + i + NP * (qy + QY * qz)];
+      X1[it] = v;
+    }
+    __syncthreads();
+    for (int it = tid; it < NV * NP3; it += kCvThreads) {
+      const int r = it / NP3, B = it - r * NP3, ij = B % (NP * NP), k = B / (NP * NP);
+      double v = 0.0;
+      for (int qz = 0; qz < NQ; ++qz) v += (a == 2 ? tx.Sd[qz][k] : tx.S[qz][k]) * X1[r * S1 + ij + NP * NP * qz];
+      Y[it] = a == 0 ? v : Y[it] + v;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // P: g = P p (velocity layout).
 template <int NPU, int NPP, int NQ, int NQY, bool ENR>
@@ -133,7 +197,9 @@ __global__ __launch_bounds__(kCvThreads) void curved_gradient_kernel(const CvArg
   constexpr auto& py = ct::tab<NPP, QY>;
   __shared__ double sp[NP3];
   __shared__ double snb[6][NPP * NPP];
-  __shared__ double F[9][NPT];
+  __shared__ double F[3][3][NPT];  // [c][a]: w|J| J^{-1}[a][c] p
+  __shared__ double pq[NPT];
+  __shared__ double X1[3 * NPU * NPU * NQ], X2[3 * NPU * QY * NQ];
   __shared__ double G[3][FMAX];
   __shared__ double acc[3 * NU3];
   __shared__ double red[3 * (kCvThreads / 64)];
@@ -155,38 +221,21 @@ __global__ __launch_bounds__(kCvThreads) void curved_gradient_kernel(const CvArg
   const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
   const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
   double ev[3] = {0.0, 0.0, 0.0};  // enrichment rows (thread partials)
+  cv_interp<NPP, NQ, QY, 1>(sp, pq, X1, X2, tid);
   for (int q = tid; q < NPT; q += kCvThreads) {
-    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
-    double v = 0.0;
-    for (int k = 0; k < NPP; ++k)
-      for (int j = 0; j < NPP; ++j) {
-        const double fy = py.S[qy][j] * px.S[qz][k];
-        for (int i = 0; i < NPP; ++i) v += px.S[qx][i] * fy * sp[i + NPP * (j + NPP * k)];
-      }
     const double* g = geo + q * 10;
-    const double wv = g[9] * v;
+    const double v = pq[q], wv = g[9] * v;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) F[a][q] = wv * g[a];  // F[3a + c] = w|J| J^{-1}[a][c] p
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[cc][a][q] = wv * g[3 * a + cc];
     if (ENR)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) ev[cc] -= g[9] * ps[q * 4 + 1 + cc] * v;
   }
   __syncthreads();
-  for (int it = tid; it < 3 * NU3; it += kCvThreads) {
-    const int cc = it / NU3, B = it - cc * NU3;
-    const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
-    double s = 0.0;
-    for (int qz = 0; qz < NQ; ++qz)
-      for (int qy = 0; qy < QY; ++qy) {
-        const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
-        const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
-        for (int qx = 0; qx < NQ; ++qx) {
-          const int q = qx + NQ * (qy + QY * qz);
-          s += ux.Sd[qx][i] * yz * F[0 + cc][q] + ux.S[qx][i] * dyz * F[3 + cc][q] + ux.S[qx][i] * ydz * F[6 + cc][q];
-        }
-      }
-    acc[it] = -s;
-  }
+  cv_project_grad<NPU, NQ, QY, 3>(&F[0][0][0], acc, X1, X2, tid);
+  for (int it = tid; it < 3 * NU3; it += kCvThreads) acc[it] = -acc[it];
   __syncthreads();
   for (int f = 0; f < 6; ++f) {
     const int d = f / 2, s = f % 2;
@@ -248,7 +297,9 @@ __global__ __launch_bounds__(kCvThreads) void curved_divergence_kernel(const CvA
   constexpr auto& py = ct::tab<NPP, QY>;
   __shared__ double su[3 * NU3];
   __shared__ double snb[6][3 * NU2];
-  __shared__ double F[3][NPT];
+  __shared__ double F[3][NPT];  // [a]: w|J| sum_d J^{-1}[a][d] u_d
+  __shared__ double T[3][NPT];
+  __shared__ double X1[3 * NPU * NPU * NQ], X2[3 * NPU * QY * NQ];
   __shared__ double G[FMAX];
   __shared__ double acc[NP3];
   __shared__ double sut[3], snut[6][3];
@@ -275,19 +326,9 @@ __global__ __launch_bounds__(kCvThreads) void curved_divergence_kernel(const CvA
   }
   const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
   const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
+  cv_interp<NPU, NQ, QY, 3>(su, &T[0][0], X1, X2, tid);
   for (int q = tid; q < NPT; q += kCvThreads) {
-    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
-    double u[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < NPU; ++k)
-      for (int j = 0; j < NPU; ++j) {
-        const double fy = uy.S[qy][j] * ux.S[qz][k];
-        for (int i = 0; i < NPU; ++i) {
-          const double b = ux.S[qx][i] * fy;
-          const int B = i + NPU * (j + NPU * k);
-#pragma unroll
-          for (int d = 0; d < 3; ++d) u[d] += b * su[d * NU3 + B];
-        }
-      }
+    double u[3] = {T[0][q], T[1][q], T[2][q]};
     if (ENR)
 #pragma unroll
       for (int d = 0; d < 3; ++d) u[d] += ps[q * 4] * sut[d];
@@ -296,20 +337,8 @@ __global__ __launch_bounds__(kCvThreads) void curved_divergence_kernel(const CvA
     for (int a = 0; a < 3; ++a) F[a][q] = g[9] * (g[3 * a] * u[0] + g[3 * a + 1] * u[1] + g[3 * a + 2] * u[2]);
   }
   __syncthreads();
-  for (int B = tid; B < NP3; B += kCvThreads) {
-    const int i = B % NPP, j = (B / NPP) % NPP, k = B / (NPP * NPP);
-    double s = 0.0;
-    for (int qz = 0; qz < NQ; ++qz)
-      for (int qy = 0; qy < QY; ++qy) {
-        const double yz = py.S[qy][j] * px.S[qz][k], dyz = py.Sd[qy][j] * px.S[qz][k];
-        const double ydz = py.S[qy][j] * px.Sd[qz][k];
-        for (int qx = 0; qx < NQ; ++qx) {
-          const int q = qx + NQ * (qy + QY * qz);
-          s += px.Sd[qx][i] * yz * F[0][q] + px.S[qx][i] * dyz * F[1][q] + px.S[qx][i] * ydz * F[2][q];
-        }
-      }
-    acc[B] = -s;
-  }
+  cv_project_grad<NPP, NQ, QY, 1>(&F[0][0], acc, X1, X2, tid);
+  for (int B = tid; B < NP3; B += kCvThreads) acc[B] = -acc[B];
   __syncthreads();
   for (int f = 0; f < 6; ++f) {
     const int d = f / 2, s = f % 2;
