@@ -125,7 +125,7 @@ __device__ __forceinline__ void cv_block_sum(double (&v)[NV], double* red, int t
 // the NQ x QY x NQ points, and the transposed gradient integrals
 //   Y[r][B] = sum_q sum_a d_a N_B(q) F[r][a][q]   (F: [NV][3][NPT]),
 // each as 1-D sweeps x, y, z; X1 (NV NP^2 NQ) and X2 (NV NP QY NQ) are scratch.
-template <int NP, int NQ, int QY, int NV>
+template <int NP, int NQ, int QY, int NV, int D = -1>  // D >= 0: the derivative d/dxi_D instead of values
 __device__ __forceinline__ void cv_interp(const double* P, double* T, double* X1, double* X2, int tid) {
   constexpr int NP3 = NP * NP * NP, NPT = NQ * QY * NQ, S1 = NP * NP * NQ, S2 = NP * QY * NQ;
   constexpr auto& tx = ct::tab<NP, NQ>;
@@ -133,21 +133,21 @@ __device__ __forceinline__ void cv_interp(const double* P, double* T, double* X1
   for (int it = tid; it < NV * S1; it += kCvThreads) {
     const int r = it / S1, t = it - r * S1, qx = t % NQ, jk = t / NQ;
     double v = 0.0;
-    for (int i = 0; i < NP; ++i) v += tx.S[qx][i] * P[r * NP3 + i + NP * jk];
+    for (int i = 0; i < NP; ++i) v += (D == 0 ? tx.Sd[qx][i] : tx.S[qx][i]) * P[r * NP3 + i + NP * jk];
     X1[it] = v;
   }
   __syncthreads();
   for (int it = tid; it < NV * S2; it += kCvThreads) {
     const int r = it / S2, t = it - r * S2, qx = t % NQ, qy = (t / NQ) % QY, k = t / (NQ * QY);
     double v = 0.0;
-    for (int j = 0; j < NP; ++j) v += ty.S[qy][j] * X1[r * S1 + qx + NQ * (j + NP * k)];
+    for (int j = 0; j < NP; ++j) v += (D == 1 ? ty.Sd[qy][j] : ty.S[qy][j]) * X1[r * S1 + qx + NQ * (j + NP * k)];
     X2[it] = v;
   }
   __syncthreads();
   for (int it = tid; it < NV * NPT; it += kCvThreads) {
     const int r = it / NPT, q = it - r * NPT, qxy = q % (NQ * QY), qz = q / (NQ * QY);
     double v = 0.0;
-    for (int k = 0; k < NP; ++k) v += tx.S[qz][k] * X2[r * S2 + qxy + NQ * QY * k];
+    for (int k = 0; k < NP; ++k) v += (D == 2 ? tx.Sd[qz][k] : tx.S[qz][k]) * X2[r * S2 + qxy + NQ * QY * k];
     T[it] = v;
   }
   __syncthreads();
@@ -407,10 +407,10 @@ __global__ __launch_bounds__(kCvThreads) void curved_divdiv_kernel(const CvArgs 
                                                                    double dt_over_cr, int layer_lo, int nlayers) {
   constexpr int QY = ENR ? NQY : NQ;
   constexpr int NU3 = NPU * NPU * NPU, NPT = NQ * QY * NQ;
-  constexpr auto& ux = ct::tab<NPU, NQ>;
-  constexpr auto& uy = ct::tab<NPU, QY>;
   __shared__ double su[3 * NU3];
-  __shared__ double F[TAU ? 1 : 9][TAU ? 1 : NPT];
+  __shared__ double B9[9][NPT];  // d u_c / d xi_a at [3a + c], then F[c][a] = J^{-1}[a][c] f at [3c + a]
+  __shared__ double X1[3 * NPU * NPU * NQ], X2[3 * NPU * QY * NQ];
+  __shared__ double acc[TAU ? 1 : 3 * NU3];
   __shared__ double red[3 * (kCvThreads / 64)];
   __shared__ double sut[3];
   const int tid = threadIdx.x;
@@ -421,20 +421,10 @@ __global__ __launch_bounds__(kCvThreads) void curved_divdiv_kernel(const CvArgs 
   const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
   const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
   if constexpr (TAU) {
+    cv_interp<NPU, NQ, QY, 3>(su, &B9[0][0], X1, X2, tid);
     double v[2] = {0.0, 0.0};  // int |u|, |e|
     for (int q = tid; q < NPT; q += kCvThreads) {
-      const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
-      double u[3] = {0.0, 0.0, 0.0};
-      for (int k = 0; k < NPU; ++k)
-        for (int j = 0; j < NPU; ++j) {
-          const double fy = uy.S[qy][j] * ux.S[qz][k];
-          for (int i = 0; i < NPU; ++i) {
-            const double b = ux.S[qx][i] * fy;
-            const int B = i + NPU * (j + NPU * k);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) u[d] += b * su[d * NU3 + B];
-          }
-        }
+      double u[3] = {B9[0][q], B9[1][q], B9[2][q]};
       if (ENR)
 #pragma unroll
         for (int d = 0; d < 3; ++d) u[d] += ps[q * 4] * sut[d];
@@ -446,59 +436,34 @@ __global__ __launch_bounds__(kCvThreads) void curved_divdiv_kernel(const CvArgs 
     if (tid == 0) A.out[c.e] = v[0] / v[1] * cbrt(v[1]) * dt_over_cr;
   } else {
     const double td = tau_d[c.e];
+    cv_interp<NPU, NQ, QY, 3, 0>(su, &B9[0][0], X1, X2, tid);
+    cv_interp<NPU, NQ, QY, 3, 1>(su, &B9[3][0], X1, X2, tid);
+    cv_interp<NPU, NQ, QY, 3, 2>(su, &B9[6][0], X1, X2, tid);
     double ev[3] = {0.0, 0.0, 0.0};
     for (int q = tid; q < NPT; q += kCvThreads) {
-      const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
-      double du[3][3] = {};  // [c][a] = d u_c / d xi_a
-      for (int k = 0; k < NPU; ++k)
-        for (int j = 0; j < NPU; ++j) {
-          const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
-          const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
-          for (int i = 0; i < NPU; ++i) {
-            const double b0 = ux.Sd[qx][i] * yz, b1 = ux.S[qx][i] * dyz, b2 = ux.S[qx][i] * ydz;
-            const int B = i + NPU * (j + NPU * k);
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-              const double uv = su[cc * NU3 + B];
-              du[cc][0] += b0 * uv;
-              du[cc][1] += b1 * uv;
-              du[cc][2] += b2 * uv;
-            }
-          }
-        }
       const double* g = geo + q * 10;
       double div = 0.0;
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) div += g[3 * a + cc] * du[cc][a];
+        for (int a = 0; a < 3; ++a) div += g[3 * a + cc] * B9[3 * a + cc][q];
       if (ENR)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) div += ps[q * 4 + 1 + cc] * sut[cc];
       const double f = g[9] * td * div;
+      // the same thread read all nine derivatives at q above
 #pragma unroll
-      for (int a = 0; a < 9; ++a) F[a][q] = g[a] * f;  // F[3a + c] = J^{-1}[a][c] f
+      for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) B9[3 * cc + a][q] = g[3 * a + cc] * f;
       if (ENR)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) ev[cc] += ps[q * 4 + 1 + cc] * f;
     }
     __syncthreads();
+    cv_project_grad<NPU, NQ, QY, 3>(&B9[0][0], acc, X1, X2, tid);
     double* o = A.out + c.e * 3 * NU3;
-    for (int it = tid; it < 3 * NU3; it += kCvThreads) {
-      const int cc = it / NU3, B = it - cc * NU3;
-      const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
-      double s = 0.0;
-      for (int qz = 0; qz < NQ; ++qz)
-        for (int qy = 0; qy < QY; ++qy) {
-          const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
-          const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
-          for (int qx = 0; qx < NQ; ++qx) {
-            const int q = qx + NQ * (qy + QY * qz);
-            s += ux.Sd[qx][i] * yz * F[cc][q] + ux.S[qx][i] * dyz * F[3 + cc][q] + ux.S[qx][i] * ydz * F[6 + cc][q];
-          }
-        }
-      o[it] = s;
-    }
+    for (int it = tid; it < 3 * NU3; it += kCvThreads) o[it] = acc[it];
     if (ENR) {
       cv_block_sum<3>(ev, red, tid);
       if (tid < 3) A.out[A.ncell * 3 * NU3 + c.enr * 3 + tid] = ev[tid];
