@@ -184,6 +184,36 @@ __device__ __forceinline__ void cv_project_grad(const double* F, double* Y, doub
   }
 }
 
+// Y[r][B] = sum_q N_B(q) F[r][q] (F: [NV][NPT]) by the transposed sweeps x, y, z.
+template <int NP, int NQ, int QY, int NV>
+__device__ __forceinline__ void cv_project_vals(const double* F, double* Y, double* X1, double* X2, int tid) {
+  constexpr int NP3 = NP * NP * NP, NPT = NQ * QY * NQ, S1 = NP * NP * NQ, S2 = NP * QY * NQ;
+  constexpr auto& tx = ct::tab<NP, NQ>;
+  constexpr auto& ty = ct::tab<NP, QY>;
+  for (int it = tid; it < NV * S2; it += kCvThreads) {
+    const int r = it / S2, t = it - r * S2, i = t % NP, qyz = t / NP;
+    const double* f = F + r * NPT + NQ * qyz;
+    double v = 0.0;
+    for (int qx = 0; qx < NQ; ++qx) v += tx.S[qx][i] * f[qx];
+    X2[it] = v;
+  }
+  __syncthreads();
+  for (int it = tid; it < NV * S1; it += kCvThreads) {
+    const int r = it / S1, t = it - r * S1, i = t % NP, j = (t / NP) % NP, qz = t / (NP * NP);
+    double v = 0.0;
+    for (int qy = 0; qy < QY; ++qy) v += ty.S[qy][j] * X2[r * S2 + i + NP * (qy + QY * qz)];
+    X1[it] = v;
+  }
+  __syncthreads();
+  for (int it = tid; it < NV * NP3; it += kCvThreads) {
+    const int r = it / NP3, B = it - r * NP3, ij = B % (NP * NP), k = B / (NP * NP);
+    double v = 0.0;
+    for (int qz = 0; qz < NQ; ++qz) v += tx.S[qz][k] * X1[r * S1 + ij + NP * NP * qz];
+    Y[it] = v;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // P: g = P p (velocity layout).
 template <int NPU, int NPP, int NQ, int NQY, bool ENR>
@@ -730,10 +760,10 @@ template <int NPU, int NQ, int NQY, bool ENR>
 __global__ __launch_bounds__(kCvThreads) void curved_vort_rhs_kernel(const CvArgs A, int layer_lo, int nlayers) {
   constexpr int QY = ENR ? NQY : NQ;
   constexpr int NU3 = NPU * NPU * NPU, NPT = NQ * QY * NQ;
-  constexpr auto& ux = ct::tab<NPU, NQ>;
-  constexpr auto& uy = ct::tab<NPU, QY>;
   __shared__ double su[3 * NU3];
-  __shared__ double F[3][NPT];
+  __shared__ double B9[9][NPT];  // d u_c / d xi_a at [3a + c]; then w|J| (curl u)_c at [c]
+  __shared__ double X1[3 * NPU * NPU * NQ], X2[3 * NPU * QY * NQ];
+  __shared__ double acc[3 * NU3];
   __shared__ double red[3 * (kCvThreads / 64)];
   __shared__ double sut[3];
   const int tid = threadIdx.x;
@@ -743,56 +773,33 @@ __global__ __launch_bounds__(kCvThreads) void curved_vort_rhs_kernel(const CvArg
   __syncthreads();
   const double* geo = A.geo + c.e * (int64_t)A.geo_stride * 10;
   const double* ps = ENR ? A.psi + c.enr * (int64_t)A.psi_pts * 4 : nullptr;
+  cv_interp<NPU, NQ, QY, 3, 0>(su, &B9[0][0], X1, X2, tid);
+  cv_interp<NPU, NQ, QY, 3, 1>(su, &B9[3][0], X1, X2, tid);
+  cv_interp<NPU, NQ, QY, 3, 2>(su, &B9[6][0], X1, X2, tid);
   double ev[3] = {0.0, 0.0, 0.0};
   for (int q = tid; q < NPT; q += kCvThreads) {
-    const int qx = q % NQ, qy = (q / NQ) % QY, qz = q / (NQ * QY);
-    double du[3][3] = {};  // [c][a] = d u_c / d xi_a
-    for (int k = 0; k < NPU; ++k)
-      for (int j = 0; j < NPU; ++j) {
-        const double yz = uy.S[qy][j] * ux.S[qz][k], dyz = uy.Sd[qy][j] * ux.S[qz][k];
-        const double ydz = uy.S[qy][j] * ux.Sd[qz][k];
-        for (int i = 0; i < NPU; ++i) {
-          const double b0 = ux.Sd[qx][i] * yz, b1 = ux.S[qx][i] * dyz, b2 = ux.S[qx][i] * ydz;
-          const int B = i + NPU * (j + NPU * k);
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc) {
-            const double uv = su[cc * NU3 + B];
-            du[cc][0] += b0 * uv;
-            du[cc][1] += b1 * uv;
-            du[cc][2] += b2 * uv;
-          }
-        }
-      }
     const double* g = geo + q * 10;
     double gr[3][3];  // [c][d] = d u_c / d x_d
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        gr[cc][d] = g[d] * du[cc][0] + g[3 + d] * du[cc][1] + g[6 + d] * du[cc][2];
+        gr[cc][d] = g[d] * B9[cc][q] + g[3 + d] * B9[3 + cc][q] + g[6 + d] * B9[6 + cc][q];
         if (ENR) gr[cc][d] += sut[cc] * ps[q * 4 + 1 + d];
       }
     const double w = g[9];
     const double cu[3] = {w * (gr[2][1] - gr[1][2]), w * (gr[0][2] - gr[2][0]), w * (gr[1][0] - gr[0][1])};
+    // the same thread read all nine derivatives at q above
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
-      F[cc][q] = cu[cc];
+      B9[cc][q] = cu[cc];
       if (ENR) ev[cc] += ps[q * 4] * cu[cc];
     }
   }
   __syncthreads();
+  cv_project_vals<NPU, NQ, QY, 3>(&B9[0][0], acc, X1, X2, tid);
   double* o = A.out + c.e * 3 * NU3;
-  for (int it = tid; it < 3 * NU3; it += kCvThreads) {
-    const int cc = it / NU3, B = it - cc * NU3;
-    const int i = B % NPU, j = (B / NPU) % NPU, k = B / (NPU * NPU);
-    double s = 0.0;
-    for (int qz = 0; qz < NQ; ++qz)
-      for (int qy = 0; qy < QY; ++qy) {
-        const double yz = uy.S[qy][j] * ux.S[qz][k];
-        for (int qx = 0; qx < NQ; ++qx) s += ux.S[qx][i] * yz * F[cc][qx + NQ * (qy + QY * qz)];
-      }
-    o[it] = s;
-  }
+  for (int it = tid; it < 3 * NU3; it += kCvThreads) o[it] = acc[it];
   if (ENR) {
     cv_block_sum<3>(ev, red, tid);
     if (tid < 3) A.out[A.ncell * 3 * NU3 + c.enr * 3 + tid] = ev[tid];
